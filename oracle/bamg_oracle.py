@@ -1,0 +1,653 @@
+"""Plain FP64 CPU oracle of the Bootstrap AMG method for Markov chains.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import or call this
+module: only the tests, the smoke check and the CPU-baseline leg of the
+benchmark use it.  It shares no code with the HIP library and imports nothing
+from the package (its counter-based generator is its own implementation of the
+published SplitMix64 definition).
+
+Every function cites the passage of Bolten, Brandt, Brannick, Frommer, Kahl and
+Livshits, "A Bootstrap Algebraic Multilevel method for Markov Chains"
+(arXiv:1004.1451) it follows.  Where the operation has a plain definition the
+code is that definition (sparse products via scipy, dense null space, pinv and
+the generalised eigenproblem via LAPACK); the setup follows Algorithm 3 and
+the interpolation Algorithm 2, step by step.  Vectorisation runs across
+independent rows or fine points only.
+
+Readings of points the paper leaves open are listed in the design notes; the
+code states each one where it is used.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+# ---------------------------------------------------------------------------
+# Counter-based generator for the initial test vectors (SplitMix64, Steele,
+# Lea and Flood 2014): h = mix(key + GAMMA), key = (seed ^ stream*GAMMA) + idx,
+# u = (h >> 11) * 2^-53.
+# ---------------------------------------------------------------------------
+_GAMMA = 0x9E3779B97F4A7C15
+_MASK = (1 << 64) - 1
+STREAM_TV = 1
+
+
+def _splitmix_u01(seed: int, stream: int, idx: np.ndarray) -> np.ndarray:
+    g = np.uint64(_GAMMA)
+    with np.errstate(over="ignore"):
+        key = (np.uint64(seed & _MASK) ^ (np.uint64(stream) * g)) + idx.astype(np.uint64)
+        z = key + g
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+
+
+def initial_tvs(n: int, r: int, seed: int) -> np.ndarray:
+    """Random initial test vectors, entry (i, k) = u(seed, TV, i*r + k) in [0,1)
+    (Section 1, step 1: r test vectors per level; uniform(0,1) reading)."""
+    idx = np.arange(n * r, dtype=np.uint64)
+    return _splitmix_u01(seed, STREAM_TV, idx).reshape(n, r)
+
+
+# ---------------------------------------------------------------------------
+# Problem (Section 2): A column stochastic, B = I - A.
+# ---------------------------------------------------------------------------
+def b_from_a(A: sp.csr_matrix) -> sp.csr_matrix:
+    """B = I - A (Section 1, eq. ax and the definition of B).  The diagonal is
+    always stored, so the structural pattern of B is that of A plus I."""
+    n = A.shape[0]
+    B = (sp.identity(n, format="csr") - A).tocsr()
+    # keep explicit zeros out of the picture: structure = pattern(A) U diag
+    pat = (abs(A).astype(bool) + sp.identity(n, format="csr", dtype=bool)).tocsr()
+    pat.sort_indices()
+    vals = np.asarray(B[pat.nonzero()]).ravel()
+    rows, cols = pat.nonzero()
+    out = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    return _with_pattern(out, pat)
+
+
+def _with_pattern(M: sp.csr_matrix, pat: sp.csr_matrix) -> sp.csr_matrix:
+    """Return M's values on exactly the structural pattern ``pat`` (entries of
+    pat absent from M are stored as explicit zeros)."""
+    pat = pat.tocsr(); pat.sort_indices()
+    Mc = M.tocsr(); Mc.sum_duplicates(); Mc.sort_indices()
+    rows = np.repeat(np.arange(pat.shape[0]), np.diff(pat.indptr))
+    vals = np.asarray(Mc[rows, pat.indices]).ravel() if pat.nnz else np.zeros(0)
+    out = sp.csr_matrix((vals.astype(np.float64), pat.indices.copy(), pat.indptr.copy()), shape=pat.shape)
+    out.has_sorted_indices = True
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Grids and full coarsening (Section 3; Section 5: every other grid point in
+# both directions).  State s = a*ny + b.
+# ---------------------------------------------------------------------------
+@dataclass(frozen=True)
+class Grid:
+    nx: int
+    ny: int
+    periodic: bool
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny
+
+    def coarse(self) -> "Grid":
+        return Grid((self.nx + 1) // 2, (self.ny + 1) // 2, self.periodic)
+
+    def can_coarsen(self) -> bool:
+        """Full coarsening keeps every coarse stencil within the 3x3 box only
+        for even periodic sides with coarse side >= 3; non-periodic sides need
+        at least two points."""
+        if self.periodic:
+            return all(m % 2 == 0 and m // 2 >= 3 for m in (self.nx, self.ny))
+        return self.nx * self.ny > 1
+
+
+def level_plan(grid: Grid, levels: int, coarse_max: int = 1024) -> list[Grid]:
+    """Grids of levels 0..L.  ``levels`` counts the finest level; 0 = coarsen
+    while n > coarse_max."""
+    plan = [grid]
+    while True:
+        g = plan[-1]
+        if levels > 0 and len(plan) >= levels:
+            break
+        if levels == 0 and g.n <= coarse_max:
+            break
+        if not g.can_coarsen():
+            if levels > 0:
+                raise ValueError("grid cannot be coarsened to the requested depth")
+            break
+        plan.append(g.coarse())
+    return plan
+
+
+def c_points(g: Grid) -> np.ndarray:
+    """Fine indices of the coarse points (a even and b even), in coarse order."""
+    a, b = np.meshgrid(np.arange(0, g.nx, 2), np.arange(0, g.ny, 2), indexing="ij")
+    return (a * g.ny + b).ravel()
+
+
+def neighbour_slots(g: Grid) -> np.ndarray:
+    """Coarse neighbourhood N_i of every point (eq. neighbor_def, read as the
+    coarse points within Chebyshev distance 1 on the grid, wrapping when
+    periodic).  Returns an (n, 4) int array of coarse indices, -1 where a slot
+    is empty, slots in lexicographic order of the offset (da, db)."""
+    cg = g.coarse()
+    a = np.arange(g.n) // g.ny
+    b = np.arange(g.n) % g.ny
+    slots = np.full((g.n, 4), -1, dtype=np.int64)
+    cnt = np.zeros(g.n, dtype=np.int64)
+    for da in (-1, 0, 1):
+        for db in (-1, 0, 1):
+            if da == 0 and db == 0:
+                continue
+            na, nb = a + da, b + db
+            if g.periodic:
+                na %= g.nx; nb %= g.ny
+                ok = np.ones(g.n, dtype=bool)
+            else:
+                ok = (na >= 0) & (na < g.nx) & (nb >= 0) & (nb < g.ny)
+            ok &= (na % 2 == 0) & (nb % 2 == 0)
+            idx = np.nonzero(ok)[0]
+            slots[idx, cnt[idx]] = (na[idx] // 2) * cg.ny + nb[idx] // 2
+            cnt[idx] += 1
+    return slots
+
+
+def is_c_point(g: Grid) -> np.ndarray:
+    s = np.arange(g.n)
+    return ((s // g.ny) % 2 == 0) & ((s % g.ny) % 2 == 0)
+
+
+# ---------------------------------------------------------------------------
+# Relaxation: omega-Jacobi, M = diag(B)/omega (Section 3, eq. amg_relax).
+# ---------------------------------------------------------------------------
+def jacobi(B: sp.csr_matrix, X: np.ndarray, omega: float, nu: int, F: np.ndarray | None = None) -> np.ndarray:
+    """nu sweeps of X <- X + omega D^-1 (F - B X), D = diag(B); F = 0 for the
+    homogeneous test-vector relaxation (Algorithm 3)."""
+    s = omega / B.diagonal()
+    s = s[:, None] if X.ndim == 2 else s
+    for _ in range(nu):
+        R = -(B @ X) if F is None else F - B @ X
+        X = X + s * R
+    return X
+
+
+def tv_weights(B: sp.csr_matrix, X: np.ndarray) -> np.ndarray:
+    """omega_k = 1/||B x_k||_2^2 (Section 3.2: the squared inverse of the
+    residual norm of B x = 0), floored at (1e-14 ||x_k||_2)^2 so that an exact
+    null vector gets a finite weight."""
+    res2 = np.sum((B @ X) ** 2, axis=0)
+    x2 = np.sum(X ** 2, axis=0)
+    return 1.0 / np.maximum(res2, 1e-28 * x2)
+
+
+# ---------------------------------------------------------------------------
+# Least-squares interpolation, Algorithm 2 (greedy choice of J_i) with the
+# functional of eq. LSfuncrowi.
+# ---------------------------------------------------------------------------
+PIVOT_RTOL = 1e-10
+
+
+def _masked_solve(G: np.ndarray, rhs: np.ndarray, S: np.ndarray) -> np.ndarray:
+    """Solve G_SS z = rhs_S per point; z = 0 outside S (batched over points)."""
+    m = S[:, :, None] & S[:, None, :]
+    M = np.where(m, G, 0.0) + np.eye(G.shape[1])[None] * (~S)[:, :, None]
+    return np.linalg.solve(M, (rhs * S)[..., None])[..., 0]
+
+
+def ls_fit(X: np.ndarray, w: np.ndarray, g: Grid, caliber: int):
+    """Interpolation P (n_f x n_c) for full coarsening.
+
+    C points get a unit row at their coarse index.  For every F point i with
+    slots N_i: G_st = sum_k w_k x_s^k x_t^k, b_s = sum_k w_k x_s^k x_i^k,
+    sigma = sum_k w_k (x_i^k)^2, so min_P L(P; S) = sigma - b_S^T G_SS^-1 b_S.
+    Greedy (Algorithm 2): starting from J = {}, add the admissible g in
+    N_i \\ J with the smallest min L(J u {g}) (strict minimum, ties to the lower
+    slot) until |J| >= c or no admissible candidate is left.  g is admissible
+    when its Schur-complement pivot G_gg - G_gJ G_JJ^-1 G_Jg exceeds
+    1e-10 G_gg.  If no slot is admissible, the first slot gets weight 1.
+    Weights p = G_JJ^-1 b_J.  Returns (P csr with ascending columns, J mask
+    (n, 4), slots (n, 4)).
+    """
+    n, R = X.shape
+    cg = g.coarse()
+    slots = neighbour_slots(g)
+    isC = is_c_point(g)
+    cpts = c_points(g)
+    fine_of_coarse = cpts                       # coarse index -> fine index
+    valid = slots >= 0
+    Xs = X[fine_of_coarse[np.where(valid, slots, 0)]]          # (n, 4, R)
+    Xs = Xs * valid[:, :, None]
+    G = np.einsum("pak,pbk,k->pab", Xs, Xs, w)
+    b = np.einsum("pak,pk,k->pa", Xs, X, w)
+    sigma = np.einsum("pk,pk,k->p", X, X, w)
+
+    J = np.zeros((n, 4), dtype=bool)
+    done = isC.copy()
+    for _ in range(4):
+        best_L = np.full(n, np.inf)
+        best_g = np.full(n, -1)
+        for s_ in range(4):
+            cand = (~done) & valid[:, s_] & (~J[:, s_]) & (J.sum(1) < caliber)
+            ix = np.nonzero(cand)[0]
+            if len(ix) == 0:
+                continue
+            Gi, bi, Ji = G[ix], b[ix], J[ix]
+            Gjg = Gi[:, :, s_]
+            piv = Gi[:, s_, s_] - np.einsum("pa,pa->p", Gjg * Ji, _masked_solve(Gi, Gjg, Ji))
+            adm = piv > PIVOT_RTOL * Gi[:, s_, s_]
+            S = Ji.copy(); S[:, s_] = True
+            L = sigma[ix] - np.einsum("pa,pa->p", bi * S, _masked_solve(Gi, bi, S))
+            better = adm & (L < best_L[ix])
+            best_L[ix] = np.where(better, L, best_L[ix])
+            best_g[ix] = np.where(better, s_, best_g[ix])
+        took = best_g >= 0
+        J[np.nonzero(took)[0], best_g[took]] = True
+        done |= ~took
+    fpts = np.nonzero((~isC) & (J.sum(1) > 0))[0]
+    p = np.zeros((n, 4))
+    p[fpts] = _masked_solve(G[fpts], b[fpts], J[fpts])
+    empty = (~isC) & (J.sum(1) == 0)
+    J[empty, 0] = True
+    p[empty, 0] = 1.0
+
+    rows, cols, vals = [], [], []
+    ci = np.nonzero(isC)[0]
+    rows.append(ci); cols.append((ci // g.ny // 2) * cg.ny + (ci % g.ny) // 2); vals.append(np.ones(len(ci)))
+    fi = np.nonzero(~isC)[0]
+    for s_ in range(4):
+        sel = fi[J[fi, s_]]
+        rows.append(sel); cols.append(slots[sel, s_]); vals.append(p[sel, s_])
+    rows = np.concatenate(rows); cols = np.concatenate(cols); vals = np.concatenate(vals)
+    P = sp.csr_matrix((vals, (rows, cols)), shape=(n, cg.n))
+    P.sort_indices()
+    # structural pattern must hold even a weight that is exactly zero
+    pat = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(n, cg.n)).astype(bool)
+    P = _with_pattern(P, pat)
+    J[isC] = False
+    return P, J, slots
+
+
+def averaging_q(P: sp.csr_matrix) -> sp.csr_matrix:
+    """Q with sparsity(Q) = sparsity(P)^T and equal entries 1/|J_i| in column i
+    (Section 4: averaging restriction, so 1^T Q = 1^T)."""
+    P = P.tocsr()
+    cnt = np.diff(P.indptr)
+    vals = np.repeat(1.0 / np.maximum(cnt, 1), cnt)
+    Pq = sp.csr_matrix((vals, P.indices.copy(), P.indptr.copy()), shape=P.shape)
+    Q = Pq.T.tocsr()
+    Q.sort_indices()
+    return Q
+
+
+def galerkin(Q: sp.csr_matrix, M: sp.csr_matrix, P: sp.csr_matrix) -> sp.csr_matrix:
+    """Petrov-Galerkin product Q (M P) (Algorithm 3: B_{l+1} = Q B P and
+    T_{l+1} = Q T P).  The stored pattern is the symbolic product of the three
+    patterns (nothing dropped, even an entry that cancels to zero)."""
+    def ones(X):
+        X = X.tocsr()
+        return sp.csr_matrix((np.ones(X.nnz), X.indices, X.indptr), shape=X.shape)
+    pat = (ones(Q) @ (ones(M) @ ones(P))).astype(bool)
+    return _with_pattern(Q @ (M @ P), pat)
+
+
+def inject(X: np.ndarray, g: Grid) -> np.ndarray:
+    """R x: the values at the coarse points (Section 1, step 4; injection)."""
+    return X[c_points(g)]
+
+
+# ---------------------------------------------------------------------------
+# Coarsest level (Algorithm 3, l = L; Section 4.2, eq. mgerrorprop).
+# ---------------------------------------------------------------------------
+@dataclass
+class EigEntry:
+    lam: complex          # eigenvalue (Im > 0 member of a conjugate pair)
+    cols: tuple           # one column (real) or two (Re, Im)
+
+
+def coarsest_svd(B: np.ndarray):
+    """Singular value decomposition of B_L.  B_L has rank n-1 (1^T B_L = 0 and
+    an irreducible fine chain), so the right singular vector of the smallest
+    singular value spans null(B_L)."""
+    return np.linalg.svd(B)
+
+
+def coarsest_null(B: np.ndarray, T: np.ndarray, svd=None) -> np.ndarray:
+    """Null vector y of B_L, scaled so that 1^T T_L y = 1."""
+    _, _, vt = coarsest_svd(B) if svd is None else svd
+    y = vt[-1].copy()
+    return y / (np.ones(len(y)) @ T @ y)
+
+
+def coarsest_pinv(B: np.ndarray, svd=None) -> np.ndarray:
+    """Moore-Penrose inverse of the rank n-1 matrix B_L: the minimal-norm
+    coarsest solve of the V-cycle (Section 4.2, after eq. mgerrorprop)."""
+    u, s, vt = coarsest_svd(B) if svd is None else svd
+    if len(s) == 1:
+        return np.zeros_like(B)
+    return (vt[:-1].T / s[:-1]) @ u[:, :-1].T
+
+
+def normalise_eigvec(v: np.ndarray) -> np.ndarray:
+    """||v||_2 = 1 and the largest-modulus entry (lowest index on ties, modulus
+    compared as re^2 + im^2) real and positive."""
+    v = v / np.sqrt(np.sum(v.real ** 2 + v.imag ** 2))
+    m2 = v.real ** 2 + v.imag ** 2
+    i = int(np.argmax(m2))
+    ph = np.conj(v[i]) / np.sqrt(m2[i])
+    return v * ph
+
+
+DENSE_EIG_MAX = 256
+
+
+def _nonzero_spectrum(B: np.ndarray, T: np.ndarray, want: int):
+    """Eigenpairs of B v = lam T v with lam != 0 and the smallest |lam|.
+
+    Small levels: the full generalised problem (QZ), dropping the null
+    eigenvalue.  Larger levels: ARPACK (implicitly restarted Arnoldi) on the
+    exact shift-invert operator v -> u with [[B, 1], [1^T T, 0]] [u; mu] =
+    [T v; 0], whose eigenvalues on {1^T T v = 0} are 1/lam; every eigenvector
+    of a nonzero lam lies in that set because 1^T B = 0."""
+    n = B.shape[0]
+    if n <= DENSE_EIG_MAX:
+        lam, vec = sla.eig(B, T)
+        order = np.argsort(np.abs(lam), kind="stable")
+        keep = order[1:]
+        return lam[keep], vec[:, keep]
+    import scipy.sparse.linalg as spla
+    K = np.zeros((n + 1, n + 1))
+    K[:n, :n] = B
+    K[:n, n] = 1.0
+    K[n, :n] = np.ones(n) @ T
+    lu = sla.lu_factor(K)
+
+    def op(v):
+        rhs = np.zeros(n + 1, dtype=np.result_type(v, np.float64))
+        rhs[:n] = T @ v
+        return sla.lu_solve(lu, rhs)[:n]
+
+    L = spla.LinearOperator((n, n), matvec=op, dtype=np.float64)
+    theta, vec = spla.eigs(L, k=min(want + 2, n - 2), which="LM", tol=1e-14,
+                           ncv=min(n - 1, max(2 * want + 10, 40)), maxiter=5000)
+    return 1.0 / theta, vec
+
+
+def coarsest_eigs(B: np.ndarray, T: np.ndarray, k: int, svd=None):
+    """The k eigenpairs of B_L x = lam T_L x of smallest |lam| (Algorithm 3,
+    l = L).  lam_0 = 0 with the null vector y; the other k-1 follow in order of
+    |lam| (a conjugate pair counts as two and is never split, so a pair at the
+    cut adds one more).  A real eigenvector gives one column, a pair the real
+    and imaginary parts of the member with Im(lam) > 0.  Returns (y, entries,
+    V) with V the real columns [y, ...]."""
+    n = B.shape[0]
+    y = coarsest_null(B, T, svd)
+    cols = [y]
+    entries = [EigEntry(0.0, (0,))]
+    if n > 1 and k > 1:
+        lam, vec = _nonzero_spectrum(B, T, k - 1)
+        # order by |lam|; conjugates are adjacent with the Im > 0 member first
+        idx = sorted(range(len(lam)), key=lambda i: (round(abs(lam[i]), 12), -np.sign(lam[i].imag), i))
+        taken, used = 0, set()
+        for j in idx:
+            if taken >= k - 1:
+                break
+            if j in used:
+                continue
+            if lam[j].imag == 0.0 or abs(lam[j].imag) <= 1e-12 * abs(lam[j]):
+                v = normalise_eigvec(vec[:, j].astype(np.complex128)).real
+                entries.append(EigEntry(complex(lam[j].real, 0.0), (len(cols),)))
+                cols.append(v)
+                taken += 1
+                used.add(j)
+            else:
+                v = vec[:, j] if lam[j].imag > 0 else np.conj(vec[:, j])
+                lj = lam[j] if lam[j].imag > 0 else np.conj(lam[j])
+                v = normalise_eigvec(v)
+                entries.append(EigEntry(complex(lj), (len(cols), len(cols) + 1)))
+                cols.append(v.real.copy()); cols.append(v.imag.copy())
+                taken += 2
+                used.add(j)
+                # the conjugate partner: the nearest eigenvalue to conj(lam_j)
+                partner = min((i for i in idx if i not in used), key=lambda i: abs(lam[i] - np.conj(lam[j])), default=None)
+                if partner is not None:
+                    used.add(partner)
+    return y, entries, np.stack(cols, axis=1)
+
+
+# ---------------------------------------------------------------------------
+# Up-leg eigenvector relaxation and eigenvalue update (Algorithm 3).
+# ---------------------------------------------------------------------------
+def eig_relax(B, T, V: np.ndarray, entries, omega: float, nu: int):
+    """Relax (B - lam_i T) x_i = 0 with omega-Jacobi, D_lam = diag(B) -
+    lam diag(T), complex arithmetic for a conjugate pair (x = Re + i Im); then
+    lam_i = <B x, x>/<T x, x> = x^H B x / x^H T x for i >= 1 (lam_0 = 0 is not
+    updated).  Returns new V and entries."""
+    V = V.copy()
+    dB = B.diagonal(); dT = T.diagonal()
+    out = []
+    for e in entries:
+        if len(e.cols) == 1:
+            x = V[:, e.cols[0]].astype(np.complex128)
+        else:
+            x = V[:, e.cols[0]] + 1j * V[:, e.cols[1]]
+        lam = e.lam
+        D = dB - lam * dT
+        for _ in range(nu):
+            x = x - omega * (B @ x - lam * (T @ x)) / D
+        if e.cols != (0,):
+            lam = np.vdot(x, B @ x) / np.vdot(x, T @ x)
+            if len(e.cols) == 1:
+                lam = complex(lam.real, 0.0)
+        if len(e.cols) == 1:
+            V[:, e.cols[0]] = x.real
+        else:
+            V[:, e.cols[0]] = x.real; V[:, e.cols[1]] = x.imag
+        out.append(EigEntry(complex(lam), e.cols))
+    return V, out
+
+
+# ---------------------------------------------------------------------------
+# Setup: the MLE cycle of Algorithm 3 (mu = 1) followed by the recomputation
+# of every P, B and T with the enriched test sets (Section 1).
+# ---------------------------------------------------------------------------
+@dataclass
+class Options:
+    levels: int = 0
+    nu_setup: int = 4
+    nu_pre: int = 2
+    nu_post: int = 2
+    omega: float = 0.7
+    caliber: int = 4
+    n_eig: int = 6
+    gmres_m: int = 50
+    seed: int = 0
+    coarse_max: int = 1024
+
+
+@dataclass
+class Level:
+    grid: Grid
+    B: sp.csr_matrix
+    T: sp.csr_matrix
+    P: sp.csr_matrix | None = None
+    Q: sp.csr_matrix | None = None
+    J: np.ndarray | None = None
+    U: np.ndarray | None = None       # relaxed random test vectors
+    V: np.ndarray | None = None       # eigenvector approximations (real columns)
+
+
+@dataclass
+class Hierarchy:
+    levels: list
+    opts: Options
+    pinv: np.ndarray
+    y: np.ndarray
+    entries: list
+    x0: np.ndarray
+    first_pass: list = field(default_factory=list)   # (P, B, T) of the down-leg
+
+
+def build_level(lv: Level, X: np.ndarray, opts: Options):
+    """One level of the hierarchy from test set X: weights, LS fit, Q,
+    B_{l+1}, T_{l+1} (Algorithm 3)."""
+    w = tv_weights(lv.B, X)
+    P, J, _ = ls_fit(X, w, lv.grid, opts.caliber)
+    Q = averaging_q(P)
+    Bc = galerkin(Q, lv.B, P)
+    Tc = galerkin(Q, lv.T, P)
+    return P, Q, J, Bc, Tc
+
+
+def setup(A: sp.csr_matrix, grid: Grid, r: int, opts: Options) -> Hierarchy:
+    n = A.shape[0]
+    plan = level_plan(grid, opts.levels, opts.coarse_max)
+    B0 = b_from_a(A.tocsr())
+    T0 = sp.identity(n, format="csr")
+    levels = [Level(plan[0], B0, T0)]
+    U = initial_tvs(n, r, opts.seed)
+    # down-leg: relax U_l, fit P_l to U_l, Galerkin products, inject U
+    for l in range(len(plan) - 1):
+        lv = levels[l]
+        U = jacobi(lv.B, U, opts.omega, opts.nu_setup)
+        lv.U = U
+        P, Q, J, Bc, Tc = build_level(lv, U, opts)
+        lv.P, lv.Q, lv.J = P, Q, J
+        levels.append(Level(plan[l + 1], Bc, Tc))
+        U = inject(U, lv.grid)
+    first = [(lv.P, lv.B, lv.T) for lv in levels]
+    # coarsest: exact eigensolve
+    cl = levels[-1]
+    cl.U = U
+    Bd, Td = cl.B.toarray(), cl.T.toarray()
+    y, entries, V = coarsest_eigs(Bd, Td, opts.n_eig)
+    cl.V = V
+    # up-leg: interpolate, relax, update the eigenvalue approximations
+    for l in range(len(plan) - 2, -1, -1):
+        lv = levels[l]
+        V = lv.P @ V
+        V, entries = eig_relax(lv.B, lv.T, V, entries, opts.omega, opts.nu_setup)
+        lv.V = V
+    x0 = levels[0].V[:, 0] / np.sum(levels[0].V[:, 0])
+    # recompute every P, B, T from the enriched sets U u V
+    for l in range(len(plan) - 1):
+        lv = levels[l]
+        X = np.concatenate([lv.U, lv.V], axis=1)
+        P, Q, J, Bc, Tc = build_level(lv, X, opts)
+        lv.P, lv.Q, lv.J = P, Q, J
+        levels[l + 1].B, levels[l + 1].T = Bc, Tc
+    cl = levels[-1]
+    Bd = cl.B.toarray()
+    svd = coarsest_svd(Bd)
+    return Hierarchy(levels, opts, coarsest_pinv(Bd, svd), coarsest_null(Bd, cl.T.toarray(), svd), entries, x0, first)
+
+
+# ---------------------------------------------------------------------------
+# Solve: V(nu1, nu2)-cycle (eq. mgerrorprop) as right preconditioner of
+# flexible GMRES on B x = 0 (Section 4.2).
+# ---------------------------------------------------------------------------
+def vcycle(h: Hierarchy, f: np.ndarray, l: int = 0) -> np.ndarray:
+    lv = h.levels[l]
+    if l == len(h.levels) - 1:
+        return h.pinv @ f
+    o = h.opts
+    e = jacobi(lv.B, np.zeros_like(f), o.omega, o.nu_pre, F=f)
+    r = f - lv.B @ e
+    ec = vcycle(h, lv.Q @ r, l + 1)
+    e = e + lv.P @ ec
+    return jacobi(lv.B, e, o.omega, o.nu_post, F=f)
+
+
+@dataclass
+class SolveInfo:
+    cycles: int = 0
+    restarts: int = 0
+    residual_l1: float = np.inf
+    clamped_mass: float = 0.0
+    history: list = field(default_factory=list)
+    converged: bool = False
+
+
+def fgmres(h: Hierarchy, x: np.ndarray, tol: float, max_cycles: int):
+    """Right-preconditioned flexible GMRES(m) for B x = 0 from x (Section 4.2;
+    the flexible form because the preconditioner is applied as given).
+    Arnoldi by modified Gram-Schmidt with one reorthogonalisation; the small
+    least-squares problem min ||beta e1 - H y|| is solved with lstsq.  Inner
+    iterations stop when the least-squares residual falls below
+    0.5 * tol * ||x||_1 * ||r0||_2 / ||r0||_1; after every restart cycle x is
+    scaled to sum one and the true ||B x||_1 / ||x||_1 decides convergence."""
+    B = h.levels[0].B
+    m = h.opts.gmres_m
+    info = SolveInfo()
+    x = x / np.sum(x)
+    while True:
+        r = -(B @ x)
+        rel = np.sum(np.abs(r)) / np.sum(np.abs(x))
+        info.residual_l1 = rel
+        info.history.append(rel)
+        if rel <= tol:
+            info.converged = True
+            break
+        if info.cycles >= max_cycles:
+            break
+        beta = np.linalg.norm(r)
+        inner_tol = 0.5 * tol * np.sum(np.abs(x)) * beta / np.sum(np.abs(r))
+        Vk = [r / beta]
+        Z = []
+        H = np.zeros((m + 1, m))
+        y = np.zeros(0)
+        for j in range(m):
+            if info.cycles >= max_cycles:
+                break
+            z = vcycle(h, Vk[j])
+            info.cycles += 1
+            w = B @ z
+            for _ in range(2):
+                for i in range(j + 1):
+                    c = np.dot(Vk[i], w)
+                    H[i, j] += c
+                    w = w - c * Vk[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            Z.append(z)
+            e1 = np.zeros(j + 2); e1[0] = beta
+            y = np.linalg.lstsq(H[: j + 2, : j + 1], e1, rcond=None)[0]
+            est = np.linalg.norm(e1 - H[: j + 2, : j + 1] @ y)
+            if H[j + 1, j] == 0.0 or est <= inner_tol:
+                break
+            Vk.append(w / H[j + 1, j])
+        if Z:
+            x = x + np.stack(Z, axis=1) @ y
+        x = x / np.sum(x)
+        info.restarts += 1
+    return x, info
+
+
+def normalise(x: np.ndarray):
+    """x >= 0 and sum(x) = 1 (Section 2: the state vector is non-negative);
+    returns the vector and the mass removed by the clamp."""
+    neg = np.sum(-x[x < 0])
+    x = np.maximum(x, 0.0)
+    return x / np.sum(x), neg
+
+
+def solve(h: Hierarchy, tol: float = 1e-10, max_cycles: int = 200, x: np.ndarray | None = None):
+    x = h.x0.copy() if x is None else x
+    x, info = fgmres(h, x, tol, max_cycles)
+    x, info.clamped_mass = normalise(x)
+    B = h.levels[0].B
+    info.residual_l1 = np.sum(np.abs(B @ x)) / np.sum(np.abs(x))
+    return x, info
+
+
+def stationary(A: sp.csr_matrix, grid: Grid, r: int, opts: Options | None = None,
+               tol: float = 1e-10, max_cycles: int = 200):
+    opts = opts or Options()
+    h = setup(A, grid, r, opts)
+    x, info = solve(h, tol, max_cycles)
+    return x, info, h
