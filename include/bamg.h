@@ -1,0 +1,207 @@
+/*
+ * bamg.h -- C ABI of the MI355X (gfx950) Bootstrap AMG library for the
+ * stationary vector of an irreducible Markov chain.
+ *
+ * Method: Bolten, Brandt, Brannick, Frommer, Kahl, Livshits, "A Bootstrap
+ * Algebraic Multilevel method for Markov Chains" (arXiv:1004.1451).
+ *   - Problem (Section 1, eq. ax; Section 2): A is column stochastic and
+ *     irreducible; find x > 0 with A x = x, i.e. B x = 0 with B = I - A.
+ *   - Setup (Algorithm 3 with mu = 1, then the recomputation of every P, B, T
+ *     described in Section 1): omega-Jacobi relaxation of r test vectors,
+ *     least-squares interpolation (Algorithm 2, eq. LSfuncrowi), averaging
+ *     restriction Q, Petrov-Galerkin B_{l+1} = Q B_l P and T_{l+1} = Q T_l P,
+ *     injection, the coarsest eigenproblem B_L x = lam T_L x, interpolation
+ *     and relaxation of the eigenvector approximations.
+ *   - Solve (Section 4.2): flexible GMRES on B x = 0, right-preconditioned by
+ *     the V(nu_pre, nu_post) cycle of eq. mgerrorprop with the minimal-norm
+ *     (Moore-Penrose) solve on the coarsest level.
+ *
+ * Conventions shared by every entry point:
+ *   - CSR of A: row = destination state, column = source state, so every
+ *     column sums to one.  Columns ascending within each row, no duplicates.
+ *     row_ptr has n+1 int32 entries, col_idx and val nnz entries.
+ *   - States lie on an nx x ny grid, state s = a*ny + b (0 <= a < nx,
+ *     0 <= b < ny); coarsening keeps the points with a and b even.  Every
+ *     nonzero of A must join states within Chebyshev distance 1 on that grid
+ *     (with wrap-around when periodic).
+ *   - "device" pointers are HIP device memory of the current device; "host"
+ *     pointers are ordinary host memory.  The library never frees caller
+ *     memory.  A handle owns everything it allocates and is bound to the
+ *     stream given at setup; it is not thread-safe.
+ *   - Return value 0 on success or a negative BAMG_E* code; no exception or
+ *     abort crosses the ABI.  bamg_last_error() gives a message for the last
+ *     failure of the calling thread.
+ */
+#ifndef BAMG_H
+#define BAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BAMG_OK 0
+#define BAMG_EINVAL (-1)        /* bad argument, shape, pattern or grid      */
+#define BAMG_ENOTSTOCH (-2)     /* negative entry or |column sum - 1| > 1e-12 */
+#define BAMG_EZERODIAG (-3)     /* b_ii <= 0 (distributive relaxation is not built) */
+#define BAMG_EUNSUPPORTED (-4)  /* stencil wider than the 3x3 grid box, or a grid
+                                   that cannot be coarsened to the requested depth */
+#define BAMG_ENOMEM (-5)        /* device allocation failed or mem_budget exceeded */
+#define BAMG_EDEVICE (-6)       /* a HIP runtime error (message kept)         */
+#define BAMG_ENOCONV (-7)       /* tolerance not reached within max_cycles; x and
+                                   info still hold the best normalised iterate */
+#define BAMG_ESINGULAR (-8)     /* coarsest pivot below 1e-12 of its column     */
+
+#define BAMG_FP64 0             /* every step in FP64                            */
+#define BAMG_MIXED 1            /* FP32 relaxation, Galerkin products and V-cycle;
+                                   FP64 norms, coarsest solve and outer iteration */
+
+#define BAMG_INTERP_LS 0        /* least-squares interpolation (Algorithm 2)     */
+#define BAMG_INTERP_MLP 1       /* learned weights with the LS fit as judge      */
+
+#define BAMG_USE_GUESS 1u       /* bamg_solve: start from the caller's x         */
+
+typedef struct bamg_ctx* bamg_handle;
+
+typedef struct {
+    int32_t nx, ny;   /* grid sides, nx*ny == n                              */
+    int32_t periodic; /* 1: wrap in both directions (sides must stay even)    */
+} bamg_grid;
+
+typedef struct {
+    int32_t levels;      /* number of levels including the finest; 0 = coarsen
+                            while n_l > coarse_max                          */
+    int32_t coarse_max;  /* used when levels == 0                             */
+    int32_t nu_setup;    /* Jacobi sweeps on test / eigenvectors per level    */
+    int32_t nu_pre, nu_post; /* V(nu_pre, nu_post) cycle                       */
+    double omega;        /* Jacobi weight (Section 3: 0.7)                    */
+    int32_t caliber;     /* c: max interpolatory points per fine point        */
+    int32_t n_eig;       /* k: coarsest eigenpairs including the null vector  */
+    int32_t arnoldi_m;   /* Krylov dimension of the coarsest eigensolve       */
+    int32_t gmres_m;     /* restart length of flexible GMRES                   */
+    int32_t precision;   /* BAMG_FP64 or BAMG_MIXED                            */
+    int32_t interp;      /* BAMG_INTERP_LS or BAMG_INTERP_MLP                  */
+    const float* mlp_weights; /* device, BAMG_MLP_NPARAM floats; needed for MLP */
+    uint64_t seed;       /* seed of the initial test vectors                  */
+    size_t mem_budget;   /* bytes; 0 = unlimited                               */
+    int32_t profile;     /* 1: time the level-0 sweeps and Galerkin products
+                            with HIP events (reported in bamg_stats)          */
+    int32_t stop_after;  /* 0: full setup; 1: after the first down-leg;
+                            2: after the coarsest eigensolve; 3: after the
+                            up-leg (inspection only)                          */
+} bamg_options;
+
+typedef struct {
+    int32_t cycles;        /* preconditioner applications (V-cycles)          */
+    int32_t restarts;      /* completed GMRES restart cycles                  */
+    int32_t converged;     /* 1 if ||B x||_1/||x||_1 <= tol                     */
+    int32_t history_len;
+    double residual_l1;    /* ||B x||_1 / ||x||_1 of the returned x (FP64)      */
+    double clamped_mass;   /* mass removed by clamping negative entries       */
+    double history[256];   /* true relative residual after each restart       */
+} bamg_solve_info;
+
+typedef struct {
+    int32_t n_levels;
+    int32_t n_v;            /* columns of eigenvector approximations          */
+    double op_complexity;   /* sum nnz(B_l) / nnz(B_0)                         */
+    double coarsest_min_pivot; /* min |pivot| / column max in the coarsest inverse */
+    double t_setup_ms, t_solve_ms;   /* host wall clock of the last calls      */
+    /* with options.profile: HIP-event time of the level-0 test-vector sweeps
+       (every launch) and Galerkin numeric products, and their launch counts */
+    double sweep_ms, galerkin_ms, lsfit_ms;
+    int32_t sweep_launches, galerkin_launches, lsfit_launches;
+    int64_t sweep_bytes, galerkin_bytes, lsfit_bytes; /* algorithmic bytes per launch */
+} bamg_stats;
+
+typedef struct {
+    int64_t n;          /* rows of B_l                                        */
+    int32_t nx, ny, periodic;
+    int64_t nnz_b, nnz_t; /* T_0 = I is not stored: nnz_t = 0 on level 0     */
+    int64_t nnz_p;      /* entries of P_l (0 on the coarsest level)           */
+    int32_t r;          /* columns of U_l                                     */
+    int32_t n_v;        /* columns of V_l                                     */
+} bamg_level_info;
+
+/* Items of bamg_export (arrays of one level, copied to host memory). */
+#define BAMG_X_B_ROWPTR 1   /* int32[n+1]                                   */
+#define BAMG_X_B_COL 2      /* int32[nnz_b]                                 */
+#define BAMG_X_B_VAL 3      /* double[nnz_b]                                */
+#define BAMG_X_T_ROWPTR 4
+#define BAMG_X_T_COL 5
+#define BAMG_X_T_VAL 6
+#define BAMG_X_P_COL 7      /* int32[4n], ELL: slot s of row i at 4i+s, -1 = empty,
+                               used slots first in ascending column order    */
+#define BAMG_X_P_VAL 8      /* double[4n]                                   */
+#define BAMG_X_U 9          /* double[n*r], row-major: the relaxed test vectors */
+#define BAMG_X_V 10         /* double[n*n_v], row-major eigenvector approximations */
+#define BAMG_X_LAMBDA 11    /* double[2*n_v]: (re, im) of the eigenvalue of each
+                               column (both columns of a pair carry the pair's
+                               Im > 0 member)                                */
+#define BAMG_X_VKIND 12     /* int32[n_v]: 0 real, 1 real part, 2 imaginary part */
+#define BAMG_X_X0 13        /* double[n]: setup's state-vector approximation */
+#define BAMG_X_W 14         /* double[n*n] (coarsest level): B_L^+ row-major   */
+#define BAMG_X_Y 15         /* double[n] (coarsest level): null vector, 1^T T y = 1 */
+#define BAMG_X_U0 16        /* double[n*r] level 0: the initial test vectors   */
+
+/* Fill *opt with the defaults: levels 0, coarse_max 1024, nu_setup 4,
+   V(2,2), omega 0.7, caliber 4, n_eig 6, arnoldi_m 64, gmres_m 50,
+   FP64, LS interpolation, seed 0, no budget, no profiling. */
+void bamg_options_default(bamg_options* opt);
+
+/* Build the hierarchy for A (device CSR, see conventions) with r initial test
+   vectors.  The caller's arrays are only read during the call and may be freed
+   once it returns.  stream: a hipStream_t (NULL = default stream); every
+   kernel of this handle runs on it.  On success *out owns the hierarchy.
+   Errors: EINVAL (null pointer, n < 1, r < 1, bad CSR, nx*ny != n),
+   ENOTSTOCH, EZERODIAG, EUNSUPPORTED, ENOMEM, EDEVICE, ESINGULAR.
+   Irreducibility is a precondition and is not checked. */
+int bamg_setup(int64_t n, const int32_t* row_ptr, const int32_t* col_idx,
+               const double* val, bamg_grid grid, int32_t r,
+               const bamg_options* opt, void* stream, bamg_handle* out);
+
+/* Solve B x = 0 to ||B x||_1 / ||x||_1 <= tol with at most max_cycles
+   preconditioner applications.  x: device, n doubles; read as the starting
+   vector with BAMG_USE_GUESS, otherwise the setup's approximation is used.
+   On return x >= 0 and sum(x) = 1.  info (host) may be NULL.  Returns 0,
+   ENOCONV (x and info hold the best iterate), EINVAL or EDEVICE.  The call
+   returns after the stream has finished. */
+int bamg_solve(bamg_handle h, double* x, double tol, int32_t max_cycles,
+               uint32_t flags, bamg_solve_info* info);
+
+/* Release everything the handle owns.  NULL is allowed. */
+int bamg_free(bamg_handle h);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* bamg_last_error(void);
+
+/* Statistics of the last setup / solve (host struct). */
+int bamg_get_stats(bamg_handle h, bamg_stats* st);
+
+/* Sizes of level l (0 = finest). */
+int bamg_level_info_get(bamg_handle h, int32_t l, bamg_level_info* out);
+
+/* Copy item `what` (BAMG_X_*) of level l into host memory dst of `bytes`
+   bytes; EINVAL if the item does not exist on that level or bytes is too
+   small.  Synchronises the handle's stream. */
+int bamg_export(bamg_handle h, int32_t l, int32_t what, void* dst, size_t bytes);
+
+/* One application of the V-cycle preconditioner on level 0: e = C f
+   (device vectors of n doubles).  Synchronises the stream. */
+int bamg_apply_vcycle(bamg_handle h, const double* f, double* e);
+
+/* nu omega-Jacobi sweeps X <- X + omega D^-1 (F - B X) on caller data
+   (Section 3, eq. amg_relax): B = I - A from device CSR of A (as in
+   bamg_setup, validated the same way), X device n x R row-major (in place),
+   F device n x R or NULL for the homogeneous problem.  Runs the same kernel
+   as the setup.  Synchronises the stream. */
+int bamg_relax(int64_t n, const int32_t* row_ptr, const int32_t* col_idx,
+               const double* val, double* X, const double* F, int32_t R,
+               double omega, int32_t nu, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BAMG_H */

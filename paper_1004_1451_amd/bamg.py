@@ -1,0 +1,220 @@
+"""Python binding of the C ABI in include/bamg.h (argument marshalling only).
+
+Every numerical step runs in the HIP library ``libbamg.so`` built in this
+directory; PyTorch only provides device memory and the stream.  Importing this
+module does not need a GPU; calling a function that launches kernels does.
+There is no fallback: if the library is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbamg.so")
+
+OK, EINVAL, ENOTSTOCH, EZERODIAG, EUNSUPPORTED, ENOMEM, EDEVICE, ENOCONV, ESINGULAR = 0, -1, -2, -3, -4, -5, -6, -7, -8
+FP64, MIXED = 0, 1
+INTERP_LS, INTERP_MLP = 0, 1
+USE_GUESS = 1
+
+X_B_ROWPTR, X_B_COL, X_B_VAL, X_T_ROWPTR, X_T_COL, X_T_VAL = 1, 2, 3, 4, 5, 6
+X_P_COL, X_P_VAL, X_U, X_V, X_LAMBDA, X_VKIND, X_X0, X_W, X_Y, X_U0 = 7, 8, 9, 10, 11, 12, 13, 14, 15, 16
+
+ERROR_NAMES = {EINVAL: "EINVAL", ENOTSTOCH: "ENOTSTOCH", EZERODIAG: "EZERODIAG", EUNSUPPORTED: "EUNSUPPORTED",
+               ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOCONV: "ENOCONV", ESINGULAR: "ESINGULAR"}
+
+# every symbol include/bamg.h declares
+EXPORTS = ["bamg_options_default", "bamg_setup", "bamg_solve", "bamg_free", "bamg_last_error", "bamg_get_stats",
+           "bamg_level_info_get", "bamg_export", "bamg_apply_vcycle", "bamg_relax"]
+
+
+class BamgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("periodic", C.c_int32)]
+
+
+class Options(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("coarse_max", C.c_int32), ("nu_setup", C.c_int32),
+                ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("omega", C.c_double),
+                ("caliber", C.c_int32), ("n_eig", C.c_int32), ("arnoldi_m", C.c_int32),
+                ("gmres_m", C.c_int32), ("precision", C.c_int32), ("interp", C.c_int32),
+                ("mlp_weights", C.c_void_p), ("seed", C.c_uint64), ("mem_budget", C.c_size_t),
+                ("profile", C.c_int32), ("stop_after", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("cycles", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
+                ("history_len", C.c_int32), ("residual_l1", C.c_double), ("clamped_mass", C.c_double),
+                ("history", C.c_double * 256)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("n_v", C.c_int32), ("op_complexity", C.c_double),
+                ("coarsest_min_pivot", C.c_double), ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double),
+                ("sweep_ms", C.c_double), ("galerkin_ms", C.c_double), ("lsfit_ms", C.c_double),
+                ("sweep_launches", C.c_int32), ("galerkin_launches", C.c_int32), ("lsfit_launches", C.c_int32),
+                ("sweep_bytes", C.c_int64), ("galerkin_bytes", C.c_int64), ("lsfit_bytes", C.c_int64)]
+
+
+class LevelInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nx", C.c_int32), ("ny", C.c_int32), ("periodic", C.c_int32),
+                ("nnz_b", C.c_int64), ("nnz_t", C.c_int64), ("nnz_p", C.c_int64), ("r", C.c_int32),
+                ("n_v", C.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libbamg.so (built by build_lib.build()); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not built: run __graft_entry__.build() or paper_1004_1451_amd/build_lib.py")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    lib.bamg_options_default.argtypes = [C.POINTER(Options)]
+    lib.bamg_options_default.restype = None
+    lib.bamg_setup.argtypes = [i64, vp, vp, vp, Grid, i32, C.POINTER(Options), vp, C.POINTER(vp)]
+    lib.bamg_setup.restype = C.c_int
+    lib.bamg_solve.argtypes = [vp, vp, dbl, i32, C.c_uint32, C.POINTER(SolveInfo)]
+    lib.bamg_solve.restype = C.c_int
+    lib.bamg_free.argtypes = [vp]
+    lib.bamg_free.restype = C.c_int
+    lib.bamg_last_error.argtypes = []
+    lib.bamg_last_error.restype = C.c_char_p
+    lib.bamg_get_stats.argtypes = [vp, C.POINTER(Stats)]
+    lib.bamg_get_stats.restype = C.c_int
+    lib.bamg_level_info_get.argtypes = [vp, i32, C.POINTER(LevelInfo)]
+    lib.bamg_level_info_get.restype = C.c_int
+    lib.bamg_export.argtypes = [vp, i32, i32, vp, C.c_size_t]
+    lib.bamg_export.restype = C.c_int
+    lib.bamg_apply_vcycle.argtypes = [vp, vp, vp]
+    lib.bamg_apply_vcycle.restype = C.c_int
+    lib.bamg_relax.argtypes = [i64, vp, vp, vp, vp, vp, i32, dbl, i32, vp]
+    lib.bamg_relax.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, allow=()):
+    if rc != OK and rc not in allow:
+        raise BamgError(rc, load().bamg_last_error().decode())
+    return rc
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    load().bamg_options_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def device_csr(chain, device="cuda"):
+    """Upload a chain's CSR arrays (row_ptr, col_idx, val) to the device."""
+    import torch
+    rp = torch.as_tensor(np.ascontiguousarray(chain.row_ptr, dtype=np.int32), device=device)
+    ci = torch.as_tensor(np.ascontiguousarray(chain.col_idx, dtype=np.int32), device=device)
+    v = torch.as_tensor(np.ascontiguousarray(chain.val, dtype=np.float64), device=device)
+    return rp, ci, v
+
+
+class Hierarchy:
+    """Owns a bamg_handle (the setup of bamg_setup)."""
+
+    def __init__(self, n, row_ptr, col_idx, val, grid, r, options: Options | None = None, stream=None):
+        lib = load()
+        self._h = C.c_void_p()
+        self.n = int(n)
+        opts = options if options is not None else default_options()
+        g = Grid(int(grid[0]), int(grid[1]), int(bool(grid[2])))
+        _check(lib.bamg_setup(self.n, C.c_void_p(row_ptr.data_ptr()), C.c_void_p(col_idx.data_ptr()),
+                              C.c_void_p(val.data_ptr()), g, int(r), C.byref(opts), _stream_ptr(stream),
+                              C.byref(self._h)))
+
+    @classmethod
+    def from_chain(cls, chain, r, options=None, stream=None):
+        rp, ci, v = device_csr(chain)
+        return cls(chain.n, rp, ci, v, (chain.nx, chain.ny, chain.periodic), r, options, stream)
+
+    def solve(self, x, tol=1e-10, max_cycles=200, use_guess=False):
+        info = SolveInfo()
+        rc = load().bamg_solve(self._h, C.c_void_p(x.data_ptr()), float(tol), int(max_cycles),
+                               USE_GUESS if use_guess else 0, C.byref(info))
+        _check(rc, allow=(ENOCONV,))
+        return info
+
+    def stats(self) -> Stats:
+        st = Stats()
+        _check(load().bamg_get_stats(self._h, C.byref(st)))
+        return st
+
+    def level_info(self, l: int) -> LevelInfo:
+        li = LevelInfo()
+        _check(load().bamg_level_info_get(self._h, int(l), C.byref(li)))
+        return li
+
+    def export(self, l: int, what: int) -> np.ndarray:
+        li = self.level_info(l)
+        n = int(li.n)
+        sizes = {X_B_ROWPTR: (n + 1, np.int32), X_B_COL: (li.nnz_b, np.int32), X_B_VAL: (li.nnz_b, np.float64),
+                 X_T_ROWPTR: (n + 1, np.int32), X_T_COL: (li.nnz_t, np.int32), X_T_VAL: (li.nnz_t, np.float64),
+                 X_P_COL: (4 * n, np.int32), X_P_VAL: (4 * n, np.float64), X_U: (n * li.r, np.float64),
+                 X_V: (n * li.n_v, np.float64), X_LAMBDA: (2 * li.n_v, np.float64), X_VKIND: (li.n_v, np.int32),
+                 X_X0: (n, np.float64), X_W: (n * n, np.float64), X_Y: (n, np.float64),
+                 X_U0: (n * li.r, np.float64)}
+        cnt, dt = sizes[what]
+        out = np.empty(int(cnt), dtype=dt)
+        _check(load().bamg_export(self._h, int(l), int(what), out.ctypes.data_as(C.c_void_p), out.nbytes))
+        return out
+
+    def apply_vcycle(self, f, e):
+        _check(load().bamg_apply_vcycle(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(e.data_ptr())))
+
+    def close(self):
+        if self._h:
+            _check(load().bamg_free(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def relax(row_ptr, col_idx, val, X, R, omega=0.7, nu=1, F=None, stream=None):
+    """nu omega-Jacobi sweeps on X (n x R, in place) for B = I - A."""
+    n = row_ptr.numel() - 1
+    _check(load().bamg_relax(n, C.c_void_p(row_ptr.data_ptr()), C.c_void_p(col_idx.data_ptr()),
+                             C.c_void_p(val.data_ptr()), C.c_void_p(X.data_ptr()),
+                             C.c_void_p(F.data_ptr()) if F is not None else None, int(R), float(omega), int(nu),
+                             _stream_ptr(stream)))
+
+
+def stationary(chain, r, tol=1e-10, max_cycles=200, **opts):
+    """Setup + solve for a chain; returns (x as a CPU numpy array, solve info, hierarchy)."""
+    import torch
+    h = Hierarchy.from_chain(chain, r, default_options(**opts))
+    x = torch.empty(chain.n, dtype=torch.float64, device="cuda")
+    info = h.solve(x, tol, max_cycles)
+    return x.cpu().numpy(), info, h

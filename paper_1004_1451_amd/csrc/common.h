@@ -1,0 +1,74 @@
+// Shared device helpers of the Bootstrap AMG library (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define BAMG_BLK 256
+#define BAMG_WAVE 64
+#define BAMG_NXCD 8        // MI355X: 8 accelerator complex dies, 32 CUs each
+
+// Workgroups are dispatched round-robin over the XCDs (block b runs on XCD
+// b % 8).  Renumber them so that each XCD owns one contiguous range of tiles:
+// stencil neighbours of a tile (rows +-ny) then sit in the same XCD's L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
+    const int per = nblocks / BAMG_NXCD, rem = nblocks % BAMG_NXCD;
+    const int x = bid % BAMG_NXCD, k = bid / BAMG_NXCD;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
+// Division of non-negative 31-bit integers by a runtime constant d >= 1:
+// q = (mulhi(x, m) + x) >> l with l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1
+// (round-up multiplier method; exact for x < 2^31).
+struct FastDiv {
+    uint32_t d, m, l;
+    FastDiv() : d(1), m(1), l(0) {}
+    explicit FastDiv(uint32_t dd) : d(dd) {
+        l = 0;
+        while ((1ull << l) < dd) ++l;
+        m = (uint32_t)((((1ull << l) - dd) << 32) / dd + 1);
+    }
+    __host__ __device__ __forceinline__ uint32_t div(uint32_t x) const {
+#ifdef __HIP_DEVICE_COMPILE__
+        uint32_t hi = __umulhi(x, m);
+#else
+        uint32_t hi = (uint32_t)(((uint64_t)x * m) >> 32);
+#endif
+        return (hi + x) >> l;
+    }
+};
+
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014) used as a counter-based
+// generator: h = mix(key + GAMMA), key = (seed ^ stream*GAMMA) + idx,
+// u = (h >> 11) * 2^-53 in [0, 1).
+__device__ __forceinline__ double splitmix_u01(uint64_t seed, uint64_t stream, uint64_t idx) {
+    const uint64_t G = 0x9E3779B97F4A7C15ull;
+    uint64_t z = ((seed ^ (stream * G)) + idx) + G;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    return (double)(z >> 11) * 0x1.0p-53;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = BAMG_WAVE / 2; off > 0; off >>= 1) v += __shfl_down(v, off, BAMG_WAVE);
+    return v;   // valid in lane 0
+}
+
+// Sum over a block of BAMG_BLK threads in a fixed order (lane tree, then the
+// four wave totals in order).  Result valid in thread 0.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x % BAMG_WAVE, w = threadIdx.x / BAMG_WAVE;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    T s = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < BAMG_BLK / BAMG_WAVE; ++i) s += sh[i];
+    return s;
+}
+
+__host__ __device__ __forceinline__ int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }

@@ -1,0 +1,715 @@
+// Dense kernels of the coarsest level (FP64, vector ALUs).
+//
+// The coarsest operator B_L (n x n, rank n-1, 1^T B_L = 0) is handled through
+// its Moore-Penrose inverse W = B_L^+ (Section 4.2: minimal-norm coarsest
+// solve), stored dense row-major with leading dimension n:
+//   1. Binv = inverse of the leading (n-1) x (n-1) block B_11 by block
+//      Gauss-Jordan without pivoting (blocks of GJ_NB);
+//   2. y = [-Binv b_{:,n}; 1] spans null(B_L);
+//   3. W = Pi_y [[Binv, 0], [0, 0]] Pi_1 with Pi_1 = I - 1 1^T / n (projector
+//      onto range(B_L) = 1^perp) and Pi_y = I - y y^T / (y^T y).
+// The coarsest eigenpairs (Algorithm 3, l = L) come from Arnoldi on the
+// shift-invert operator v -> u - y (c^T u)/(c^T y), u = W T v, c = T^T 1,
+// whose eigenvalues on {c^T v = 0} are 1/lam for the nonzero lam.
+#pragma once
+#include "common.h"
+
+#define GJ_NB 64
+
+// Dense copy of a CSR matrix (n x n, ld n); zero first.
+__global__ void k_densify(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                          const double* __restrict__ v, double* __restrict__ D) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) D[(size_t)i * n + ci[p]] = v[p];
+}
+
+template <typename M>
+__global__ void k_densify_cast(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                               const M* __restrict__ v, double* __restrict__ D) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) D[(size_t)i * n + ci[p]] = (double)v[p];
+}
+
+__global__ void k_fill(long long n, double val, double* __restrict__ a) {
+    long long i = (long long)blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i < n) a[i] = val;
+}
+
+// Max |entry| of a dense matrix: partial per block, then a fixed-order final.
+__global__ void k_absmax_partial(long long n, const double* __restrict__ a, double* __restrict__ part) {
+    __shared__ double sh[BAMG_BLK];
+    double m = 0;
+    for (long long i = (long long)blockIdx.x * BAMG_BLK + threadIdx.x; i < n; i += (long long)gridDim.x * BAMG_BLK)
+        m = fmax(m, fabs(a[i]));
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = BAMG_BLK / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// In-place inverse of the diagonal block A[k0:k0+nb, k0:k0+nb] (ld) by
+// Gauss-Jordan without pivoting, in LDS.  Records min |pivot| / scale in
+// *minpiv (scale = max |B_L| entry; a single block runs this kernel).
+__global__ void __launch_bounds__(BAMG_BLK)
+k_gj_diag(int ld, int k0, int nb, double* __restrict__ A, const double* __restrict__ scale,
+          double* __restrict__ minpiv) {
+    __shared__ double S[GJ_NB][GJ_NB + 1];
+    __shared__ double prow[GJ_NB + 1];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < nb * nb; e += BAMG_BLK) {
+        int r = e / nb, c = e % nb;
+        S[r][c] = A[(size_t)(k0 + r) * ld + k0 + c];
+    }
+    __syncthreads();
+    double mp = 1e300;
+    for (int k = 0; k < nb; ++k) {
+        double piv = S[k][k];
+        if (tid == 0) mp = fmin(mp, fabs(piv) / *scale);
+        double ip = 1.0 / piv;
+        // scaled pivot row (column k becomes 1/piv)
+        if (tid < nb) prow[tid] = (tid == k) ? ip : S[k][tid] * ip;
+        __syncthreads();
+        for (int e = tid; e < nb * nb; e += BAMG_BLK) {
+            int r = e / nb, c = e % nb;
+            if (r == k) continue;
+            double f = S[r][k];
+            S[r][c] = (c == k) ? -f * ip : S[r][c] - f * prow[c];
+        }
+        __syncthreads();
+        if (tid < nb) S[k][tid] = prow[tid];
+        __syncthreads();
+    }
+    for (int e = tid; e < nb * nb; e += BAMG_BLK) {
+        int r = e / nb, c = e % nb;
+        A[(size_t)(k0 + r) * ld + k0 + c] = S[r][c];
+    }
+    if (tid == 0) *minpiv = fmin(*minpiv, mp);
+}
+
+// Row panel: A[k0:k0+nb, j] = Dinv * A[k0:k0+nb, j] for j outside the block.
+// Block = 64 columns.
+__global__ void __launch_bounds__(BAMG_BLK)
+k_gj_rowpanel(int m, int ld, int k0, int nb, double* __restrict__ A) {
+    __shared__ double D[GJ_NB][GJ_NB + 1];
+    __shared__ double X[GJ_NB][GJ_NB + 1];
+    const int tid = threadIdx.x;
+    int j0 = blockIdx.x * 64;
+    if (j0 >= k0 && j0 < k0 + nb) return;   // the diagonal block (aligned to 64)
+    int w = min(64, m - j0);
+    for (int e = tid; e < nb * nb; e += BAMG_BLK) D[e / nb][e % nb] = A[(size_t)(k0 + e / nb) * ld + k0 + e % nb];
+    for (int e = tid; e < nb * 64; e += BAMG_BLK) {
+        int r = e / 64, c = e % 64;
+        X[r][c] = c < w ? A[(size_t)(k0 + r) * ld + j0 + c] : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < nb * 64; e += BAMG_BLK) {
+        int r = e / 64, c = e % 64;
+        if (c >= w) continue;
+        double s = 0;
+        for (int k = 0; k < nb; ++k) s += D[r][k] * X[k][c];
+        A[(size_t)(k0 + r) * ld + j0 + c] = s;
+    }
+}
+
+// Rank-nb update of every block outside row block and column block k:
+// A[i, j] -= A[i, k-block] * A[k-block, j].  64 x 64 tiles, 4 x 4 per thread.
+__global__ void __launch_bounds__(BAMG_BLK)
+k_gj_update(int m, int ld, int k0, int nb, double* __restrict__ A) {
+    __shared__ double As[64][GJ_NB + 1];
+    __shared__ double Bs[GJ_NB][64 + 1];
+    const int tiles = ceil_div(m, 64);
+    int t = xcd_tile(blockIdx.x, gridDim.x);
+    int ti = t / tiles, tj = t % tiles;
+    int i0 = ti * 64, j0 = tj * 64;
+    if (i0 == k0 || j0 == k0) return;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < 64 * nb; e += BAMG_BLK) {
+        int r = e / nb, c = e % nb;
+        As[r][c] = (i0 + r < m) ? A[(size_t)(i0 + r) * ld + k0 + c] : 0.0;
+    }
+    for (int e = tid; e < nb * 64; e += BAMG_BLK) {
+        int r = e / 64, c = e % 64;
+        Bs[r][c] = (j0 + c < m) ? A[(size_t)(k0 + r) * ld + j0 + c] : 0.0;
+    }
+    __syncthreads();
+    const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0;
+    for (int k = 0; k < nb; ++k) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) av[a] = As[tr + a][k];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bv[b] = Bs[k][tc + b];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        int i = i0 + tr + a;
+        if (i >= m) continue;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            int j = j0 + tc + b;
+            if (j < m) A[(size_t)i * ld + j] -= acc[a][b];
+        }
+    }
+}
+
+// Column panel: A[i, k-block] = -A[i, k-block] * Dinv for rows outside the
+// block.  Block = 64 rows.
+__global__ void __launch_bounds__(BAMG_BLK)
+k_gj_colpanel(int m, int ld, int k0, int nb, double* __restrict__ A) {
+    __shared__ double D[GJ_NB][GJ_NB + 1];
+    __shared__ double X[64][GJ_NB + 1];
+    const int tid = threadIdx.x;
+    int i0 = blockIdx.x * 64;
+    if (i0 == k0) return;
+    int h = min(64, m - i0);
+    for (int e = tid; e < nb * nb; e += BAMG_BLK) D[e / nb][e % nb] = A[(size_t)(k0 + e / nb) * ld + k0 + e % nb];
+    for (int e = tid; e < 64 * nb; e += BAMG_BLK) {
+        int r = e / nb, c = e % nb;
+        X[r][c] = r < h ? A[(size_t)(i0 + r) * ld + k0 + c] : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < 64 * nb; e += BAMG_BLK) {
+        int r = e / nb, c = e % nb;
+        if (r >= h) continue;
+        double s = 0;
+        for (int k = 0; k < nb; ++k) s += X[r][k] * D[k][c];
+        A[(size_t)(i0 + r) * ld + k0 + c] = -s;
+    }
+}
+
+// y = alpha * A x (+ beta * y0) for a dense row-major n x n matrix: one
+// wavefront per row, fixed-order reduction.
+__global__ void __launch_bounds__(BAMG_BLK)
+k_gemv(int rows, int cols, int ld, const double* __restrict__ A, const double* __restrict__ x,
+       double* __restrict__ y) {
+    int row = blockIdx.x * (BAMG_BLK / BAMG_WAVE) + threadIdx.x / BAMG_WAVE;
+    int lane = threadIdx.x % BAMG_WAVE;
+    if (row >= rows) return;
+    const double* a = A + (size_t)row * ld;
+    double s = 0;
+    for (int j = lane; j < cols; j += BAMG_WAVE) s += a[j] * x[j];
+    s = wave_sum(s);
+    if (lane == 0) y[row] = s;
+}
+
+// FP32 copy of the coarse inverse for the mixed-precision cycle.
+__global__ void __launch_bounds__(BAMG_BLK)
+k_gemv_f32(int rows, int cols, int ld, const float* __restrict__ A, const float* __restrict__ x,
+           float* __restrict__ y) {
+    int row = blockIdx.x * (BAMG_BLK / BAMG_WAVE) + threadIdx.x / BAMG_WAVE;
+    int lane = threadIdx.x % BAMG_WAVE;
+    if (row >= rows) return;
+    const float* a = A + (size_t)row * ld;
+    float s = 0;
+    for (int j = lane; j < cols; j += BAMG_WAVE) s += a[j] * x[j];
+    s = wave_sum(s);
+    if (lane == 0) y[row] = s;
+}
+
+// y^T A: column-weighted sums, one thread per column (coalesced rows).
+__global__ void k_gemv_t(int rows, int cols, int ld, const double* __restrict__ A, const double* __restrict__ y,
+                         double* __restrict__ out) {
+    int j = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (j >= cols) return;
+    double s = 0;
+    for (int i = 0; i < rows; ++i) s += y[i] * A[(size_t)i * ld + j];
+    out[j] = s;
+}
+
+// Null vector from the inverse of B_11: y_1 = -Binv b_col, y_n = 1 (the GEMV
+// result is passed in g).
+__global__ void k_null_finish(int n, const double* __restrict__ g, double* __restrict__ y) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i < n - 1) y[i] = -g[i];
+    if (i == n - 1) y[i] = 1.0;
+}
+
+// W <- W - s 1^T / n - y (u - (y^T s) 1^T / n)^T / (y^T y): both projections
+// of the padded inverse at once (s = W 1, u = y^T W, sc[0] = y^T s,
+// sc[1] = y^T y).
+__global__ void k_project_w(int n, double* __restrict__ W, const double* __restrict__ s, const double* __restrict__ u,
+                            const double* __restrict__ y, const double* __restrict__ sc) {
+    long long e = (long long)blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (e >= (long long)n * n) return;
+    int i = (int)(e / n), j = (int)(e % n);
+    double inv_n = 1.0 / n;
+    W[e] = W[e] - s[i] * inv_n - y[i] * (u[j] - sc[0] * inv_n) / sc[1];
+}
+
+// ---------------------------------------------------------------- small vectors
+// Fixed-order dot products for vectors of the coarsest level (one block).
+__global__ void k_dot1(int n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out) {
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    double s = 0;
+    for (int i = threadIdx.x; i < n; i += BAMG_BLK) s += a[i] * b[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) *out = s;
+}
+
+// ---------------------------------------------------------------- Arnoldi
+// The Krylov basis Vb (n x (m+1), column j at j*n) and the Hessenberg matrix
+// H ((m+1) x m, column-major ld m+1) live on the device.  One Arnoldi step is
+//   w = T v_j (CSR, or copy when T = I), u = W w, u -= y (c^T u)/(c^T y),
+//   two rounds of classical Gram-Schmidt, h_{j+1,j} = ||u||, v_{j+1} = u/h.
+// Multi-dot: blocks = j+1, block b computes <v_b, u>.
+__global__ void k_mdot(int n, int nv, const double* __restrict__ Vb, const double* __restrict__ u,
+                       double* __restrict__ h) {
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    int b = blockIdx.x;
+    if (b >= nv) return;
+    double s = 0;
+    for (int i = threadIdx.x; i < n; i += BAMG_BLK) s += Vb[(size_t)b * n + i] * u[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) h[b] = s;
+}
+
+// u -= sum_b h_b v_b; hacc_b += h_b.
+__global__ void k_mupdate(int n, int nv, const double* __restrict__ Vb, const double* __restrict__ h,
+                          double* __restrict__ u, double* __restrict__ hacc) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i < n) {
+        double s = u[i];
+        for (int b = 0; b < nv; ++b) s -= h[b] * Vb[(size_t)b * n + i];
+        u[i] = s;
+    }
+    if (blockIdx.x == 0 && (int)threadIdx.x < nv) hacc[threadIdx.x] += h[threadIdx.x];
+}
+
+// u -= y * (c^T u) / (c^T y)   (dots precomputed: d[0] = c^T u, cy = c^T y).
+__global__ void k_project_domain(int n, const double* __restrict__ y, const double* __restrict__ d,
+                                 const double* __restrict__ cy, double* __restrict__ u) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i < n) u[i] -= y[i] * (*d / *cy);
+}
+
+// v = u / sqrt(nrm2); H[j+1, j] = sqrt(nrm2).
+__global__ void k_normalize_into(int n, const double* __restrict__ u, const double* __restrict__ nrm2,
+                                 double* __restrict__ v, double* __restrict__ hout) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    double nr = sqrt(*nrm2);
+    if (i < n) v[i] = nr > 0 ? u[i] / nr : 0.0;
+    if (i == 0) *hout = nr;
+}
+
+// ---------------------------------------------------------------- Hessenberg eigensolver
+// Eigenpairs of the m x m Hessenberg matrix H_m of the Arnoldi process, with
+// one wavefront (64 lanes, m <= 64), data in LDS.
+//  - Eigenvalues: Francis double-shift QR iteration (implicit bulge chase with
+//    3x3 Householder reflectors; deflation when a subdiagonal entry falls
+//    below eps times its diagonal neighbours; exceptional shifts after 10 and
+//    20 stagnant iterations).  The scalar control flow runs redundantly in
+//    every lane; the row and column updates of each reflector are spread over
+//    the lanes (lane j owns column j of a row update, lane i row i of a
+//    column update).
+//  - Eigenvectors of the selected eigenvalues: inverse iteration with the
+//    complex matrix H - theta I (Gaussian elimination with pivoting between
+//    adjacent rows, tiny pivots replaced by 1e-14 ||H||).
+#define HQR_MAXM 64
+#define HQR_LD (HQR_MAXM + 1)
+
+__device__ __forceinline__ void lds_sync() { __syncthreads(); }
+
+__device__ void hqr_wave(int m, double* A, double* wr, double* wi, int* fail) {
+    const int lane = threadIdx.x;
+    const double eps = 2.220446049250313e-16;
+#define AA(i, j) A[(i) * HQR_LD + (j)]
+    double anorm = 0;
+    for (int i = 0; i < m; ++i)
+        for (int j = (i > 0 ? i - 1 : 0); j < m; ++j) anorm += fabs(AA(i, j));
+    int nn = m - 1;
+    double t = 0.0;
+    int its_total = 0;
+    while (nn >= 0) {
+        int its = 0, l;
+        do {
+            for (l = nn; l >= 1; --l) {
+                double s = fabs(AA(l - 1, l - 1)) + fabs(AA(l, l));
+                if (s == 0.0) s = anorm;
+                if (fabs(AA(l, l - 1)) <= eps * s) break;
+            }
+            lds_sync();
+            if (l >= 1 && lane == 0) AA(l, l - 1) = 0.0;
+            lds_sync();
+            double x = AA(nn, nn);
+            if (l == nn) {
+                if (lane == 0) { wr[nn] = x + t; wi[nn] = 0.0; }
+                --nn;
+            } else {
+                double y = AA(nn - 1, nn - 1);
+                double w = AA(nn, nn - 1) * AA(nn - 1, nn);
+                if (l == nn - 1) {
+                    double p = 0.5 * (y - x), q = p * p + w, z = sqrt(fabs(q));
+                    x += t;
+                    if (lane == 0) {
+                        if (q >= 0.0) {
+                            z = p + (p >= 0 ? fabs(z) : -fabs(z));
+                            wr[nn - 1] = wr[nn] = x + z;
+                            if (z != 0.0) wr[nn] = x - w / z;
+                            wi[nn - 1] = wi[nn] = 0.0;
+                        } else {
+                            wr[nn - 1] = wr[nn] = x + p;
+                            wi[nn - 1] = -z; wi[nn] = z;
+                        }
+                    }
+                    nn -= 2;
+                } else {
+                    if (its >= 60 || its_total > 60 * m) { *fail = 1; lds_sync(); return; }
+                    if (its == 10 || its == 20) {
+                        t += x;
+                        lds_sync();
+                        if (lane <= nn) AA(lane, lane) -= x;
+                        lds_sync();
+                        double s = fabs(AA(nn, nn - 1)) + fabs(AA(nn - 1, nn - 2));
+                        y = x = 0.75 * s;
+                        w = -0.4375 * s * s;
+                    }
+                    ++its; ++its_total;
+                    int mm;
+                    double p = 0, q = 0, r = 0, z;
+                    for (mm = nn - 2; mm >= l; --mm) {
+                        z = AA(mm, mm);
+                        r = x - z;
+                        double s = y - z;
+                        p = (r * s - w) / AA(mm + 1, mm) + AA(mm, mm + 1);
+                        q = AA(mm + 1, mm + 1) - z - r - s;
+                        r = AA(mm + 2, mm + 1);
+                        s = fabs(p) + fabs(q) + fabs(r);
+                        p /= s; q /= s; r /= s;
+                        if (mm == l) break;
+                        double u = fabs(AA(mm, mm - 1)) * (fabs(q) + fabs(r));
+                        double v = fabs(p) * (fabs(AA(mm - 1, mm - 1)) + fabs(z) + fabs(AA(mm + 1, mm + 1)));
+                        if (u <= eps * v) break;
+                    }
+                    lds_sync();
+                    if (lane >= mm + 2 && lane <= nn) {
+                        AA(lane, lane - 2) = 0.0;
+                        if (lane != mm + 2) AA(lane, lane - 3) = 0.0;
+                    }
+                    lds_sync();
+                    for (int k = mm; k <= nn - 1; ++k) {
+                        if (k != mm) {
+                            p = AA(k, k - 1);
+                            q = AA(k + 1, k - 1);
+                            r = (k != nn - 1) ? AA(k + 2, k - 1) : 0.0;
+                            x = fabs(p) + fabs(q) + fabs(r);
+                            if (x == 0.0) continue;
+                            p /= x; q /= x; r /= x;
+                        }
+                        double s = sqrt(p * p + q * q + r * r);
+                        if (p < 0) s = -s;
+                        lds_sync();
+                        if (lane == 0) {
+                            if (k == mm) {
+                                if (l != mm) AA(k, k - 1) = -AA(k, k - 1);
+                            } else {
+                                AA(k, k - 1) = -s * x;
+                            }
+                        }
+                        p += s;
+                        double hx = p / s, hy = q / s, hz = r / s;
+                        double qq = q / p, rr = r / p;
+                        lds_sync();
+                        {   // rows k..k+2, columns k..nn
+                            int j = lane;
+                            if (j >= k && j <= nn) {
+                                double pp = AA(k, j) + qq * AA(k + 1, j);
+                                if (k != nn - 1) {
+                                    pp += rr * AA(k + 2, j);
+                                    AA(k + 2, j) -= pp * hz;
+                                }
+                                AA(k + 1, j) -= pp * hy;
+                                AA(k, j) -= pp * hx;
+                            }
+                        }
+                        lds_sync();
+                        {   // columns k..k+2, rows l..min(nn, k+3)
+                            int mmin = nn < k + 3 ? nn : k + 3;
+                            int i = lane;
+                            if (i >= l && i <= mmin) {
+                                double pp = hx * AA(i, k) + hy * AA(i, k + 1);
+                                if (k != nn - 1) {
+                                    pp += hz * AA(i, k + 2);
+                                    AA(i, k + 2) -= pp * rr;
+                                }
+                                AA(i, k + 1) -= pp * qq;
+                                AA(i, k) -= pp;
+                            }
+                        }
+                        lds_sync();
+                    }
+                }
+            }
+            lds_sync();
+        } while (l < nn - 1);
+    }
+#undef AA
+}
+
+// Packed upper triangle (complex): row k, column j >= k.
+__device__ __forceinline__ int upk(int m, int k, int j) { return k * m - (k * (k - 1)) / 2 + (j - k); }
+
+// z <- (H - theta I)^-1 z for the Hessenberg H (global, row-major m x m),
+// one wavefront; U (LDS, packed, 2 doubles per entry), z (LDS, complex).
+__device__ void hess_shift_solve_wave(int m, const double* __restrict__ H, double thr, double thi,
+                                      double* U, double* zr, double* zi, double hnorm) {
+    const int lane = threadIdx.x;
+    const double tiny = 1e-14 * hnorm;
+    // current row k, lane j holds entry j
+    double cr = 0, ci = 0;
+    if (lane < m) { cr = H[lane] - (lane == 0 ? thr : 0.0); ci = (lane == 0 ? -thi : 0.0); }
+    for (int k = 0; k < m - 1; ++k) {
+        double nr = 0, ni = 0;
+        if (lane >= k && lane < m) {
+            nr = H[(size_t)(k + 1) * m + lane] - (lane == k + 1 ? thr : 0.0);
+            ni = (lane == k + 1 ? -thi : 0.0);
+        }
+        double ckr = __shfl(cr, k, BAMG_WAVE), cki = __shfl(ci, k, BAMG_WAVE);
+        double nkr = __shfl(nr, k, BAMG_WAVE), nki = __shfl(ni, k, BAMG_WAVE);
+        lds_sync();
+        bool swap = nkr * nkr + nki * nki > ckr * ckr + cki * cki;
+        if (swap) {
+            double tr = cr, ti = ci; cr = nr; ci = ni; nr = tr; ni = ti;
+            double a = ckr, b = cki; ckr = nkr; cki = nki; nkr = a; nki = b;
+            if (lane == 0) {
+                double t0 = zr[k], t1 = zi[k];
+                zr[k] = zr[k + 1]; zi[k] = zi[k + 1]; zr[k + 1] = t0; zi[k + 1] = t1;
+            }
+        }
+        if (ckr * ckr + cki * cki < tiny * tiny) {
+            ckr = tiny; cki = 0.0;
+            if (lane == k) { cr = tiny; ci = 0.0; }
+        }
+        double d = ckr * ckr + cki * cki;
+        double fr = (nkr * ckr + nki * cki) / d, fi = (nki * ckr - nkr * cki) / d;
+        lds_sync();
+        if (lane >= k && lane < m) {
+            int e = upk(m, k, lane);
+            U[2 * e] = cr; U[2 * e + 1] = ci;
+            // next row minus f times the pivot row
+            double ar = nr - (fr * cr - fi * ci), ai = ni - (fr * ci + fi * cr);
+            cr = ar; ci = ai;
+        } else {
+            cr = 0; ci = 0;
+        }
+        if (lane == 0) {
+            double zkr = zr[k], zki = zi[k];
+            zr[k + 1] -= fr * zkr - fi * zki;
+            zi[k + 1] -= fr * zki + fi * zkr;
+        }
+        lds_sync();
+    }
+    {
+        int k = m - 1;
+        double ckr = __shfl(cr, k, BAMG_WAVE), cki = __shfl(ci, k, BAMG_WAVE);
+        if (ckr * ckr + cki * cki < tiny * tiny) { ckr = tiny; cki = 0.0; }
+        if (lane == k) { int e = upk(m, k, k); U[2 * e] = ckr; U[2 * e + 1] = cki; }
+    }
+    lds_sync();
+    for (int i = m - 1; i >= 0; --i) {
+        double sr = 0, si = 0;
+        if (lane > i && lane < m) {
+            int e = upk(m, i, lane);
+            double ur = U[2 * e], ui = U[2 * e + 1];
+            sr = ur * zr[lane] - ui * zi[lane];
+            si = ur * zi[lane] + ui * zr[lane];
+        }
+        sr = wave_sum(sr); si = wave_sum(si);
+        sr = __shfl(sr, 0, BAMG_WAVE); si = __shfl(si, 0, BAMG_WAVE);
+        lds_sync();
+        if (lane == 0) {
+            int e = upk(m, i, i);
+            double ur = U[2 * e], ui = U[2 * e + 1];
+            double ar = zr[i] - sr, ai = zi[i] - si;
+            double d = ur * ur + ui * ui;
+            zr[i] = (ar * ur + ai * ui) / d;
+            zi[i] = (ai * ur - ar * ui) / d;
+        }
+        lds_sync();
+    }
+}
+
+// One wavefront: eigenvalues theta of H_m (Hessenberg, column-major (m+1) x m
+// in Hh), selection of the `want` nonzero lam = 1/theta of smallest |lam|
+// (largest |theta|; a conjugate pair counts as two and is never split, so one
+// more at a split; among equal moduli the member with Im(lam) > 0 first),
+// eigenvectors of H for the selected ones.  Outputs:
+//   nsel_out[0] = selected entries, [1] = real columns they need, [2] = fail;
+//   sel_lam[2e..2e+1] = lam of entry e (Im >= 0 member of a pair);
+//   sel_s[e*2m + 2j..] = (re, im) of the eigenvector of H for entry e.
+// Hrow: scratch m*m doubles (row-major copy of H_m).
+__global__ void __launch_bounds__(BAMG_WAVE)
+k_hessenberg_eig(int m, int want, const double* __restrict__ Hh, double* __restrict__ Hrow,
+                 int* __restrict__ nsel_out, double* __restrict__ sel_lam, double* __restrict__ sel_s) {
+    __shared__ double A[HQR_MAXM * HQR_LD];
+    __shared__ double wr[HQR_MAXM], wi[HQR_MAXM], zr[HQR_MAXM], zi[HQR_MAXM];
+    __shared__ int used[HQR_MAXM];
+    __shared__ int fail;
+    const int lane = threadIdx.x;
+    if (lane == 0) fail = 0;
+    double hn = 0;
+    for (int i = 0; i < m; ++i) {
+        double v = 0;
+        if (lane < m) v = (i <= lane + 1) ? Hh[(size_t)lane * (m + 1) + i] : 0.0;
+        if (lane < m) { A[i * HQR_LD + lane] = v; Hrow[(size_t)i * m + lane] = v; }
+        hn = fmax(hn, fabs(v));
+    }
+    // max over lanes
+#pragma unroll
+    for (int off = BAMG_WAVE / 2; off > 0; off >>= 1) hn = fmax(hn, __shfl_xor(hn, off, BAMG_WAVE));
+    if (lane < HQR_MAXM) used[lane] = 0;
+    __threadfence_block();
+    lds_sync();
+    hqr_wave(m, A, wr, wi, &fail);
+    lds_sync();
+    int taken = 0, ne = 0, ncols = 0;
+    while (taken < want && !fail) {
+        int best = -1;
+        double bm = -1;
+        for (int i = 0; i < m; ++i) {
+            if (used[i]) continue;
+            double mod = wr[i] * wr[i] + wi[i] * wi[i];
+            if (best < 0 || mod > bm * (1 + 1e-12) || (mod >= bm * (1 - 1e-12) && wi[i] < wi[best])) { best = i; bm = mod; }
+        }
+        if (best < 0 || bm == 0.0) break;
+        bool pair = wi[best] != 0.0;
+        double thr = wr[best], thi = pair ? -fabs(wi[best]) : 0.0;
+        int pj = -1;
+        if (pair) {
+            double bd = 1e300;
+            for (int i = 0; i < m; ++i) {
+                if (used[i] || i == best) continue;
+                double d = (wr[i] - thr) * (wr[i] - thr) + (wi[i] + thi) * (wi[i] + thi);
+                if (d < bd) { bd = d; pj = i; }
+            }
+        }
+        lds_sync();
+        if (lane == 0) { used[best] = 1; if (pj >= 0) used[pj] = 1; }
+        if (lane < m) { zr[lane] = 1.0; zi[lane] = 0.0; }
+        lds_sync();
+        for (int itn = 0; itn < 3; ++itn) {
+            hess_shift_solve_wave(m, Hrow, thr, thi, A, zr, zi, hn);
+            double s = lane < m ? zr[lane] * zr[lane] + zi[lane] * zi[lane] : 0.0;
+            s = wave_sum(s);
+            s = __shfl(s, 0, BAMG_WAVE);
+            double nr = sqrt(s);
+            lds_sync();
+            if (lane < m) { zr[lane] /= nr; zi[lane] /= nr; }
+            lds_sync();
+        }
+        double den = thr * thr + thi * thi;
+        if (lane == 0) {
+            sel_lam[2 * ne] = thr / den;
+            sel_lam[2 * ne + 1] = pair ? -thi / den : 0.0;
+        }
+        if (lane < m) {
+            sel_s[(size_t)ne * m * 2 + 2 * lane] = zr[lane];
+            sel_s[(size_t)ne * m * 2 + 2 * lane + 1] = pair ? zi[lane] : 0.0;
+        }
+        ++ne;
+        ncols += pair ? 2 : 1;
+        taken += pair ? 2 : 1;
+        lds_sync();
+    }
+    if (lane == 0) { nsel_out[0] = ne; nsel_out[1] = ncols; nsel_out[2] = fail; }
+}
+
+// Ritz vector of entry e: v = Vb[:, 0:m] s_e (complex), into out_re / out_im.
+__global__ void k_ritz(int n, int m, const double* __restrict__ Vb, const double* __restrict__ s,
+                       double* __restrict__ out_re, double* __restrict__ out_im) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    double a = 0, b = 0;
+    for (int j = 0; j < m; ++j) {
+        double v = Vb[(size_t)j * n + i];
+        a += v * s[2 * j]; b += v * s[2 * j + 1];
+    }
+    out_re[i] = a; out_im[i] = b;
+}
+
+// Normalise a (complex) coarsest eigenvector: ||v||_2 = 1 and the entry of
+// largest re^2 + im^2 (lowest index on ties) real and positive.  One block.
+// Writes the real part to column c of V (ld R) and, for a pair, the
+// imaginary part to column c+1.
+__global__ void k_eigvec_normalise(int n, const double* __restrict__ vr, const double* __restrict__ vi, int pair,
+                                   double* __restrict__ V, int R, int c) {
+    __shared__ double sh[BAMG_BLK];
+    __shared__ int shi[BAMG_BLK];
+    __shared__ double shs[BAMG_BLK / BAMG_WAVE];
+    double s = 0, best = -1;
+    int bi = 0;
+    for (int i = threadIdx.x; i < n; i += BAMG_BLK) {
+        double m2 = vr[i] * vr[i] + (pair ? vi[i] * vi[i] : 0.0);
+        s += m2;
+        if (m2 > best) { best = m2; bi = i; }
+    }
+    s = block_sum(s, shs);
+    __syncthreads();
+    sh[threadIdx.x] = best; shi[threadIdx.x] = bi;
+    __syncthreads();
+    for (int st = BAMG_BLK / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            double o = sh[threadIdx.x + st];
+            int oi = shi[threadIdx.x + st];
+            if (o > sh[threadIdx.x] || (o == sh[threadIdx.x] && oi < shi[threadIdx.x])) { sh[threadIdx.x] = o; shi[threadIdx.x] = oi; }
+        }
+        __syncthreads();
+    }
+    __shared__ double fac[2];
+    if (threadIdx.x == 0) {
+        int im = shi[0];
+        double ar = vr[im], ai = pair ? vi[im] : 0.0;
+        double mod = sqrt(ar * ar + ai * ai);
+        double nrm = sqrt(s);
+        // multiply by conj(v_m)/|v_m| / ||v||
+        fac[0] = ar / mod / nrm; fac[1] = -ai / mod / nrm;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += BAMG_BLK) {
+        double a = vr[i], b = pair ? vi[i] : 0.0;
+        double nr = a * fac[0] - b * fac[1], ni = a * fac[1] + b * fac[0];
+        V[(size_t)i * R + c] = nr;
+        if (pair) V[(size_t)i * R + c + 1] = ni;
+    }
+}
+
+// Column 0 of V: y / (c^T y).
+__global__ void k_scale_into_col(int n, const double* __restrict__ y, const double* __restrict__ cy,
+                                 double* __restrict__ V, int R, int c) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i < n) V[(size_t)i * R + c] = y[i] / *cy;
+}
+
+// Eigenvalue / column-kind tables of V from the selection (one thread).
+__global__ void k_eig_tables(const int* __restrict__ nsel, const double* __restrict__ sel_lam,
+                             double* __restrict__ lam, int* __restrict__ kind, int* __restrict__ ent_col) {
+    if (threadIdx.x != 0) return;
+    int ne = nsel[0];
+    lam[0] = 0; lam[1] = 0; kind[0] = 0; ent_col[0] = 0;
+    int c = 1;
+    for (int e = 0; e < ne; ++e) {
+        double lr = sel_lam[2 * e], li = sel_lam[2 * e + 1];
+        ent_col[e + 1] = c;
+        if (li != 0.0) {
+            lam[2 * c] = lr; lam[2 * c + 1] = li; kind[c] = 1;
+            lam[2 * c + 2] = lr; lam[2 * c + 3] = li; kind[c + 1] = 2;
+            c += 2;
+        } else {
+            lam[2 * c] = lr; lam[2 * c + 1] = 0; kind[c] = 0;
+            c += 1;
+        }
+    }
+}

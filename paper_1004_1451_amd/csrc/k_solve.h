@@ -1,0 +1,218 @@
+// Kernels of the outer iteration (flexible GMRES in FP64) and generic
+// fixed-order reductions.
+#pragma once
+#include "common.h"
+
+enum RedOp : int { RED_DOT = 0, RED_ABS = 1, RED_SUM = 2, RED_NEGSUM = 3 };
+
+// Stage 1 of a reduction over n entries: fixed partition (grid-stride with a
+// fixed grid), per-block sum in a fixed order.
+template <int OP>
+__global__ void k_reduce_partial(long long n, const double* __restrict__ a, const double* __restrict__ b,
+                                 double* __restrict__ part) {
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    double s = 0;
+    for (long long i = (long long)blockIdx.x * BAMG_BLK + threadIdx.x; i < n; i += (long long)gridDim.x * BAMG_BLK) {
+        double v = a[i];
+        if (OP == RED_DOT) s += v * b[i];
+        else if (OP == RED_ABS) s += fabs(v);
+        else if (OP == RED_SUM) s += v;
+        else s += v < 0 ? -v : 0.0;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void k_reduce_final(int nparts, const double* __restrict__ part, double* __restrict__ out) {
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    double s = 0;
+    for (int j = threadIdx.x; j < nparts; j += BAMG_BLK) s += part[j];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) *out = s;
+}
+
+// Multi-dot h_b = <V_b, w> for b < nv (V: nv vectors of length n, stride n):
+// stage 1 over a fixed row partition -> part[block][nv].
+__global__ void k_mdot_partial(int n, int nv, const double* __restrict__ V, const double* __restrict__ w,
+                               double* __restrict__ part) {
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    for (int b = 0; b < nv; ++b) {
+        double s = 0;
+        for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < n; i += gridDim.x * BAMG_BLK)
+            s += V[(size_t)b * n + i] * w[i];
+        s = block_sum(s, sh);
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * nv + b] = s;
+    }
+}
+
+// Stage 2: h[b] = sum_blocks part[.][b]; hacc[b] += h[b] (hacc may be null).
+__global__ void k_mdot_final(int nparts, int nv, const double* __restrict__ part, double* __restrict__ h,
+                             double* __restrict__ hacc) {
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    int b = blockIdx.x;
+    double s = 0;
+    for (int j = threadIdx.x; j < nparts; j += BAMG_BLK) s += part[(size_t)j * nv + b];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) {
+        h[b] = s;
+        if (hacc) hacc[b] += s;
+    }
+}
+
+// w -= sum_b h_b V_b.
+__global__ void k_vupdate(int n, int nv, const double* __restrict__ V, const double* __restrict__ h,
+                          double* __restrict__ w) {
+    int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    double s = w[i];
+    for (int b = 0; b < nv; ++b) s -= h[b] * V[(size_t)b * n + i];
+    w[i] = s;
+}
+
+// out = a * scale where scale = num / den (device scalars; den null -> 1).
+__global__ void k_scale(int n, const double* __restrict__ a, const double* __restrict__ num,
+                        const double* __restrict__ den, int sqrt_den, double* __restrict__ out) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    double d = den ? (sqrt_den ? sqrt(*den) : *den) : 1.0;
+    double s = (num ? *num : 1.0) / d;
+    out[i] = a[i] * s;
+}
+
+__global__ void k_copy(long long n, const double* __restrict__ a, double* __restrict__ b) {
+    long long i = (long long)blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+// One column of the GMRES Hessenberg matrix (column-major, ld): apply the
+// previous Givens rotations, form the new one, update g; est = |g[j+1]|.
+// hnew2 = ||w||^2 after orthogonalisation (device scalar).
+__global__ void k_givens(int j, int ld, double* __restrict__ H, const double* __restrict__ hnew2,
+                         double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
+                         double* __restrict__ est) {
+    if (threadIdx.x != 0) return;
+    double* col = H + (size_t)j * ld;
+    col[j + 1] = sqrt(*hnew2);
+    for (int i = 0; i < j; ++i) {
+        double a = col[i], b = col[i + 1];
+        col[i] = cs[i] * a + sn[i] * b;
+        col[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    double a = col[j], b = col[j + 1];
+    double r = sqrt(a * a + b * b);
+    double c = r > 0 ? a / r : 1.0, s = r > 0 ? b / r : 0.0;
+    cs[j] = c; sn[j] = s;
+    col[j] = r; col[j + 1] = 0.0;
+    g[j + 1] = -s * g[j];
+    g[j] = c * g[j];
+    *est = fabs(g[j + 1]);
+}
+
+// Back substitution R y = g for the k x k upper triangle of H (one thread).
+__global__ void k_gmres_y(int k, int ld, const double* __restrict__ H, const double* __restrict__ g,
+                          double* __restrict__ y) {
+    if (threadIdx.x != 0) return;
+    for (int i = k - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int c = i + 1; c < k; ++c) s -= H[(size_t)c * ld + i] * y[c];
+        y[i] = s / H[(size_t)i * ld + i];
+    }
+}
+
+// x += sum_j y_j Z_j.
+__global__ void k_xupdate(int n, int k, const double* __restrict__ Z, const double* __restrict__ y,
+                          double* __restrict__ x) {
+    int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    double s = x[i];
+    for (int j = 0; j < k; ++j) s += y[j] * Z[(size_t)j * n + i];
+    x[i] = s;
+}
+
+// g = [beta, 0, ...]; H zeroed by the caller.
+__global__ void k_gmres_init(int m, const double* __restrict__ beta2, double* __restrict__ g) {
+    int i = threadIdx.x;
+    for (int k = i; k <= m; k += blockDim.x) g[k] = 0.0;
+    if (i == 0) g[0] = sqrt(*beta2);
+}
+
+// x <- max(x, 0).
+__global__ void k_clamp(int n, double* __restrict__ x) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i < n && x[i] < 0) x[i] = 0.0;
+}
+
+// Initial Arnoldi vector of the coarsest eigensolve (seeded, stream 7).
+__global__ void k_rand_vec(int n, uint64_t seed, double* __restrict__ v) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i < n) v[i] = splitmix_u01(seed, 7ull, (uint64_t)i) - 0.5;
+}
+
+// c_j = sum_i T_ij (column sums of a coarse operator whose stencil lies in
+// the 3x3 box): gather row i of T for every box neighbour i of j, fixed
+// order.  T == identity when trp is null.
+template <typename M>
+__global__ void k_colsum_box(int n, FastDiv dy, int nx, int ny, int periodic, const int* __restrict__ trp,
+                             const int* __restrict__ tci, const M* __restrict__ tv, double* __restrict__ c) {
+    int j = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (j >= n) return;
+    if (!trp) { c[j] = 1.0; return; }
+    int ja = (int)dy.div((uint32_t)j), jb = j - ja * ny;
+    int rows[9];
+#pragma unroll
+    for (int s = 0; s < 9; ++s) {
+        int a = ja + s / 3 - 1, b = jb + s % 3 - 1;
+        rows[s] = -1;
+        if (periodic) {
+            a = a < 0 ? a + nx : (a >= nx ? a - nx : a);
+            b = b < 0 ? b + ny : (b >= ny ? b - ny : b);
+        } else if (a < 0 || a >= nx || b < 0 || b >= ny) {
+            continue;
+        }
+        rows[s] = a * ny + b;
+    }
+    double s = 0;
+    // ascending row order
+    for (int pass = 0; pass < 9; ++pass) {
+        int best = -1;
+        for (int t = 0; t < 9; ++t) {
+            if (rows[t] < 0) continue;
+            int rank = 0;
+            for (int u = 0; u < 9; ++u) rank += rows[u] >= 0 && rows[u] < rows[t];
+            if (rank == pass) best = rows[t];
+        }
+        if (best < 0) break;
+        for (int p = trp[best]; p < trp[best + 1]; ++p)
+            if (tci[p] == j) s += (double)tv[p];
+    }
+    c[j] = s;
+}
+
+// out[i] = V[i*R + c] widened to FP64.
+template <typename T>
+__global__ void k_get_col_t(int rows, int R, int c, const T* __restrict__ V, double* __restrict__ out) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i < rows) out[i] = (double)V[(size_t)i * R + c];
+}
+
+// Copy column col of a dense row-major matrix (rows x ld) into out.
+__global__ void k_get_col(int rows, int ld, int col, const double* __restrict__ A, double* __restrict__ out) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i < rows) out[i] = A[(size_t)i * ld + col];
+}
+
+// Zero the last row and column of an n x n dense matrix.
+__global__ void k_zero_border(int n, double* __restrict__ A) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i < n) { A[(size_t)(n - 1) * n + i] = 0.0; A[(size_t)i * n + n - 1] = 0.0; }
+}
+
+// Cast a level vector between the FP64 outer iteration and the FP32 cycle.
+__global__ void k_d2f(int n, const double* __restrict__ a, float* __restrict__ b) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+__global__ void k_f2d(int n, const float* __restrict__ a, double* __restrict__ b) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i < n) b[i] = (double)a[i];
+}

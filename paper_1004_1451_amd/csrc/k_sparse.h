@@ -1,0 +1,784 @@
+// Sparse kernels of the Bootstrap AMG setup and cycle.
+//
+// Layouts (device):
+//   B_l, T_l : CSR, int32 row_ptr / col (ascending), values of type M.
+//   X (test vectors, eigenvector approximations): n x R row-major, R values of
+//              one state contiguous ("interleaved").
+//   P_l      : ELL-4, slot s of fine row i at 4i+s; -1 marks an empty slot;
+//              used slots first, ascending coarse column.
+//   Q_l      : ELL-9, slot s of coarse row I at 9I+s, fine columns ascending.
+#pragma once
+#include "common.h"
+
+enum : int {
+    ERR_RANGE = 1,      // column index out of range / not ascending / bad row_ptr
+    ERR_NEG = 2,        // negative or non-finite entry
+    ERR_WIDE = 4,       // entry joins states farther apart than the 3x3 box
+    ERR_COLSUM = 8,     // |column sum - 1| > 1e-12
+    ERR_ZERODIAG = 16,  // b_ii <= 0
+};
+
+struct GridDev {
+    int nx, ny, periodic;
+    FastDiv dy;          // division by ny
+};
+
+// Signed offset a2 - a1 on a side of length m, wrapped into [-m/2, m/2] when
+// periodic.
+__device__ __forceinline__ int grid_delta(int a1, int a2, int m, int periodic) {
+    int d = a2 - a1;
+    if (periodic) {
+        if (d > m / 2) d -= m;
+        else if (d < -(m / 2)) d += m;
+    }
+    return d;
+}
+
+// ---------------------------------------------------------------- B = I - A
+// Pass 1: validate row i of A and count the entries of row i of B (a missing
+// diagonal is inserted).  Column sums accumulate with atomics: the check is a
+// tolerance test, so the summation order does not matter.
+__global__ void k_check_a(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                          const double* __restrict__ v, GridDev g, int nnz,
+                          double* __restrict__ colsum, int* __restrict__ cnt, int* __restrict__ err) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    int p0 = rp[i], p1 = rp[i + 1];
+    int e = 0;
+    if (p0 < 0 || p1 < p0 || p1 > nnz) { atomicOr(err, ERR_RANGE); cnt[i] = 1; return; }
+    int ia = (int)g.dy.div((uint32_t)i), ib = i - ia * g.ny;
+    bool has_diag = false;
+    int prev = -1;
+    for (int p = p0; p < p1; ++p) {
+        int j = ci[p];
+        double a = v[p];
+        if (j < 0 || j >= n || j <= prev) { e |= ERR_RANGE; break; }
+        prev = j;
+        if (!(a >= 0.0) || !(a <= 1.0 + 1e-12)) e |= ERR_NEG;
+        int ja = (int)g.dy.div((uint32_t)j), jb = j - ja * g.ny;
+        int da = grid_delta(ia, ja, g.nx, g.periodic), db = grid_delta(ib, jb, g.ny, g.periodic);
+        if (da < -1 || da > 1 || db < -1 || db > 1) e |= ERR_WIDE;
+        if (j == i) has_diag = true;
+        atomicAdd(&colsum[j], a);
+    }
+    if (e) atomicOr(err, e);
+    cnt[i] = (p1 - p0) + (has_diag ? 0 : 1);
+}
+
+__global__ void k_check_colsum(int n, const double* __restrict__ colsum, int* __restrict__ err) {
+    int j = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (j >= n) return;
+    if (!(fabs(colsum[j] - 1.0) <= 1e-12)) atomicOr(err, ERR_COLSUM);
+}
+
+// Pass 2: write row i of B = I - A and dinv_i = omega / b_ii.
+template <typename M>
+__global__ void k_build_b(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                          const double* __restrict__ v, const int* __restrict__ brp,
+                          int* __restrict__ bci, double* __restrict__ bv, M* __restrict__ bv_lo,
+                          double omega, double* __restrict__ dinv, M* __restrict__ dinv_lo,
+                          int* __restrict__ err) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    int q = brp[i];
+    bool done = false;
+    double diag = 1.0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int j = ci[p];
+        if (!done && j > i) { bci[q] = i; bv[q] = 1.0; ++q; done = true; }
+        if (j == i) { diag = 1.0 - v[p]; bci[q] = i; bv[q] = diag; done = true; }
+        else { bci[q] = j; bv[q] = -v[p]; }
+        ++q;
+    }
+    if (!done) { bci[q] = i; bv[q] = 1.0; }
+    if (bv_lo) for (int p = brp[i]; p < brp[i + 1]; ++p) bv_lo[p] = (M)bv[p];
+    if (!(diag > 0.0)) atomicOr(err, ERR_ZERODIAG);
+    dinv[i] = omega / diag;
+    if (dinv_lo) dinv_lo[i] = (M)(omega / diag);
+}
+
+// dinv_i = omega / b_ii for a coarse operator (diagonal always stored, since
+// every coarse row holds its own C point).
+template <typename M>
+__global__ void k_dinv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                       const M* __restrict__ v, double omega, M* __restrict__ dinv, int* __restrict__ err) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    M d = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+        if (ci[p] == i) d = v[p];
+    if (!(d > (M)0)) atomicOr(err, ERR_ZERODIAG);
+    dinv[i] = (M)(omega / (double)d);
+}
+
+// ---------------------------------------------------------------- scan
+// Exclusive prefix sum of int32 counts in three passes (block sums, scan of
+// the block sums in one block, add).  out has n+1 entries.
+__global__ void k_scan_block(int n, const int* __restrict__ in, int* __restrict__ out, int* __restrict__ bsum) {
+    __shared__ int sh[BAMG_BLK];
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    int v = i < n ? in[i] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < BAMG_BLK; off <<= 1) {
+        int t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    if (i < n) out[i] = sh[threadIdx.x] - v;
+    if (threadIdx.x == BAMG_BLK - 1) bsum[blockIdx.x] = sh[threadIdx.x];
+}
+
+__global__ void k_scan_sums(int nb, int* __restrict__ bsum, int* __restrict__ total) {
+    __shared__ int sh[BAMG_BLK];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nb; base += BAMG_BLK) {
+        int i = base + threadIdx.x;
+        int v = i < nb ? bsum[i] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < BAMG_BLK; off <<= 1) {
+            int t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nb) bsum[i] = carry + sh[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == BAMG_BLK - 1) carry += sh[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void k_scan_add(int n, int* __restrict__ out, const int* __restrict__ bsum, const int* __restrict__ total) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i < n) out[i] += bsum[blockIdx.x];
+    if (i == 0) out[n] = *total;
+}
+
+// ---------------------------------------------------------------- relaxation
+// X_out = X_in + dinv (F - B X_in) on R interleaved columns (omega-Jacobi,
+// Section 3).  One thread per (row, column); a wavefront covers 64/R rows and
+// every stencil offset reads a contiguous run of X.  F == nullptr: homogeneous.
+template <typename T, typename M>
+__global__ void __launch_bounds__(BAMG_BLK)
+k_sweep(int n, int R, FastDiv divR, const int* __restrict__ rp, const int* __restrict__ ci,
+        const M* __restrict__ v, const M* __restrict__ dinv, const T* __restrict__ X,
+        const T* __restrict__ F, T* __restrict__ Y) {
+    int t = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (t >= n * R) return;
+    int i = (int)divR.div((uint32_t)t), k = t - i * R;
+    int p0 = rp[i], p1 = rp[i + 1];
+    T acc = 0;
+    for (int p = p0; p < p1; ++p) acc += (T)v[p] * X[(size_t)ci[p] * R + k];
+    T r = (F ? F[t] : (T)0) - acc;
+    Y[t] = X[t] + (T)dinv[i] * r;
+}
+
+// First smoothing sweep from a zero guess: e = dinv * f.
+template <typename T, typename M>
+__global__ void k_jacobi_zero(int n, const M* __restrict__ dinv, const T* __restrict__ f, T* __restrict__ e) {
+    int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (i < n) e[i] = (T)dinv[i] * f[i];
+}
+
+// r = f - B e (single column).
+template <typename T, typename M>
+__global__ void __launch_bounds__(BAMG_BLK)
+k_residual(int n, const int* __restrict__ rp, const int* __restrict__ ci, const M* __restrict__ v,
+           const T* __restrict__ e, const T* __restrict__ f, T* __restrict__ r) {
+    int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    T acc = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) acc += (T)v[p] * e[ci[p]];
+    r[i] = (f ? f[i] : (T)0) - acc;
+}
+
+// y = alpha * B x with FP64 vectors (values widened), used by the outer
+// iteration and the coarsest eigensolve.
+template <typename M>
+__global__ void __launch_bounds__(BAMG_BLK)
+k_spmv(int n, const int* __restrict__ rp, const int* __restrict__ ci, const M* __restrict__ v,
+       const double* __restrict__ x, double alpha, double* __restrict__ y) {
+    int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) acc += (double)v[p] * x[ci[p]];
+    y[i] = alpha * acc;
+}
+
+// f_c = Q r (restriction, ELL-9).
+template <typename T, typename M>
+__global__ void k_restrict(int nc, const int* __restrict__ qc, const M* __restrict__ qv,
+                           const T* __restrict__ r, T* __restrict__ fc) {
+    int I = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (I >= nc) return;
+    T acc = 0;
+#pragma unroll
+    for (int s = 0; s < 9; ++s) {
+        int i = qc[(size_t)I * 9 + s];
+        if (i >= 0) acc += (T)qv[(size_t)I * 9 + s] * r[i];
+    }
+    fc[I] = acc;
+}
+
+// e += P e_c (prolongation, ELL-4).
+template <typename T, typename M>
+__global__ void k_prolong_add(int n, const int* __restrict__ pc, const M* __restrict__ pv,
+                              const T* __restrict__ ec, T* __restrict__ e) {
+    int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    T acc = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        int J = pc[(size_t)i * 4 + s];
+        if (J >= 0) acc += (T)pv[(size_t)i * 4 + s] * ec[J];
+    }
+    e[i] += acc;
+}
+
+// V_f = P V_c on R interleaved columns (interpolation of the eigenvector
+// approximations, Algorithm 3).
+template <typename T, typename M>
+__global__ void k_interp(int n, int R, FastDiv divR, const int* __restrict__ pc, const M* __restrict__ pv,
+                         const T* __restrict__ Vc, T* __restrict__ Vf) {
+    int t = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (t >= n * R) return;
+    int i = (int)divR.div((uint32_t)t), k = t - i * R;
+    T acc = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        int J = pc[(size_t)i * 4 + s];
+        if (J >= 0) acc += (T)pv[(size_t)i * 4 + s] * Vc[(size_t)J * R + k];
+    }
+    Vf[t] = acc;
+}
+
+// ---------------------------------------------------------------- TV weights
+// Stage 1: partial sums over a fixed partition of rows of (B x_k)_i^2 and
+// (x_k)_i^2 for every column k of X = [U | V] (U: Ru columns, V: Rv columns).
+// blockDim = R * floor(256 / R) so that a thread keeps its column across the
+// grid-stride loop.  part: [gridDim][2R] doubles.
+template <typename T, typename M>
+__global__ void k_colnorm_partial(int n, int Ru, int Rv, FastDiv divR, const int* __restrict__ rp,
+                                  const int* __restrict__ ci, const M* __restrict__ v,
+                                  const T* __restrict__ U, const T* __restrict__ V,
+                                  double* __restrict__ part) {
+    __shared__ double shr[BAMG_BLK], shx[BAMG_BLK];
+    const int R = Ru + Rv;
+    const long long total = (long long)n * R;
+    const int stride = gridDim.x * blockDim.x;
+    double sr = 0, sx = 0;
+    int k = -1;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        int i = (int)divR.div((uint32_t)t);
+        k = (int)(t - (long long)i * R);
+        const T* Xp = k < Ru ? U : V;
+        int ld = k < Ru ? Ru : Rv, kk = k < Ru ? k : k - Ru;
+        double acc = 0;
+        for (int p = rp[i]; p < rp[i + 1]; ++p) acc += (double)v[p] * (double)Xp[(size_t)ci[p] * ld + kk];
+        double x = (double)Xp[(size_t)i * ld + kk];
+        sr += acc * acc;
+        sx += x * x;
+    }
+    shr[threadIdx.x] = sr;
+    shx[threadIdx.x] = sx;
+    __syncthreads();
+    if ((int)threadIdx.x < R) {
+        double a = 0, b = 0;
+        for (int j = threadIdx.x; j < (int)blockDim.x; j += R) { a += shr[j]; b += shx[j]; }
+        // thread c reduces column (blockIdx.x*blockDim.x + c) % R
+        int col = (int)(((long long)blockIdx.x * blockDim.x + threadIdx.x) % R);
+        part[(size_t)blockIdx.x * 2 * R + col] = a;
+        part[(size_t)blockIdx.x * 2 * R + R + col] = b;
+    }
+}
+
+// Stage 2: one block per column, fixed-order reduction over the partials;
+// w_k = 1 / max(||B x_k||^2, (1e-14 ||x_k||)^2) (Section 3.2).
+__global__ void k_colnorm_final(int nparts, int R, const double* __restrict__ part, double* __restrict__ w,
+                                double* __restrict__ res2_out) {
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    int k = blockIdx.x;
+    double a = 0, b = 0;
+    for (int j = threadIdx.x; j < nparts; j += BAMG_BLK) {
+        a += part[(size_t)j * 2 * R + k];
+        b += part[(size_t)j * 2 * R + R + k];
+    }
+    a = block_sum(a, sh);
+    b = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        double den = a > 1e-28 * b ? a : 1e-28 * b;
+        w[k] = 1.0 / den;
+        if (res2_out) res2_out[k] = a;
+    }
+}
+
+// ---------------------------------------------------------------- LS fit
+// Masked Cholesky of the 4x4 Gram G on the slot set S (bit mask), slot order.
+// Fills lower factor L (entries outside S untouched / zero) and returns false
+// if a pivot is not positive.  z = L^-1 b on S; log-free determinant product.
+__device__ __forceinline__ bool chol4(const double G[4][4], const double b[4], int S, double L[4][4],
+                                      double z[4], double& det) {
+    det = 1.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) L[i][j] = 0.0;
+        z[i] = 0.0;
+    }
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (!((S >> j) & 1)) continue;
+        double d = G[j][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+        if (!(d > 0.0)) { ok = false; d = 1.0; }
+        det *= d;
+        double lj = sqrt(d);
+        L[j][j] = lj;
+        double zz = b[j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) zz -= L[j][k] * z[k];
+        z[j] = zz / lj;
+#pragma unroll
+        for (int i = j + 1; i < 4; ++i) {
+            if (!((S >> i) & 1)) continue;
+            double s = G[i][j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+            L[i][j] = s / lj;
+        }
+    }
+    return ok;
+}
+
+// Least-squares interpolation, Algorithm 2 with the functional of eq.
+// LSfuncrowi, one thread per fine point of level l.  X = [U | V]
+// (Ru + Rv columns), weights w (device, R).  C point (a, b even): unit row at
+// its coarse index, and with inject != nullptr its U row is copied to the
+// coarse test vectors (injection, Algorithm 3).  F point: slots N_i = coarse
+// points within Chebyshev distance 1, in lexicographic order of (da, db);
+// G_st = sum_k w_k x_s^k x_t^k, b_s = sum_k w_k x_s^k x_i^k, sigma; greedy:
+// add the admissible candidate with the smallest sigma - b_S^T G_SS^-1 b_S
+// (strict minimum, ties to the lower slot) until |J| >= caliber; a candidate
+// g is admissible when det(G_{J+g}) / det(G_J) > 1e-10 G_gg (its Schur
+// complement pivot).  Gram and solves in FP64 whatever the storage type.
+template <typename T, typename MP>
+__global__ void __launch_bounds__(BAMG_BLK)
+k_ls_fit(int n, GridDev g, int ncy, int Ru, int Rv, const T* __restrict__ U, const T* __restrict__ V,
+         const double* __restrict__ w, int caliber, int* __restrict__ pc, MP* __restrict__ pv,
+         T* __restrict__ inject, int* __restrict__ jmask) {
+    int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    const int ia = (int)g.dy.div((uint32_t)i), ib = i - ia * g.ny;
+    if (((ia | ib) & 1) == 0) {
+        int I = (ia >> 1) * ncy + (ib >> 1);
+        pc[(size_t)i * 4] = I; pv[(size_t)i * 4] = (MP)1;
+#pragma unroll
+        for (int s = 1; s < 4; ++s) { pc[(size_t)i * 4 + s] = -1; pv[(size_t)i * 4 + s] = (MP)0; }
+        if (inject)
+            for (int k = 0; k < Ru; ++k) inject[(size_t)I * Ru + k] = U[(size_t)i * Ru + k];
+        if (jmask) jmask[i] = 0;
+        return;
+    }
+    // neighbourhood slots
+    int sf[4], sc[4];
+    int ns = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) { sf[s] = i; sc[s] = -1; }
+#pragma unroll
+    for (int da = -1; da <= 1; ++da)
+#pragma unroll
+        for (int db = -1; db <= 1; ++db) {
+            if (da == 0 && db == 0) continue;
+            int na = ia + da, nb = ib + db;
+            if (g.periodic) {
+                na = na < 0 ? na + g.nx : (na >= g.nx ? na - g.nx : na);
+                nb = nb < 0 ? nb + g.ny : (nb >= g.ny ? nb - g.ny : nb);
+            } else if (na < 0 || na >= g.nx || nb < 0 || nb >= g.ny) {
+                continue;
+            }
+            if (((na | nb) & 1) != 0) continue;
+            // at most 4 coarse points in the box; ns < 4 always holds here
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                if (s == ns) { sf[s] = na * g.ny + nb; sc[s] = (na >> 1) * ncy + (nb >> 1); }
+            ++ns;
+        }
+    int valid = (1 << ns) - 1;
+    // weighted Gram, right-hand side and sigma over all test vectors
+    double G[4][4], b[4], sigma = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        b[s] = 0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) G[s][t] = 0;
+    }
+    for (int k = 0; k < Ru + Rv; ++k) {
+        const T* Xp = k < Ru ? U : V;
+        int ld = k < Ru ? Ru : Rv, kk = k < Ru ? k : k - Ru;
+        double wk = w[k];
+        double xi = (double)Xp[(size_t)i * ld + kk];
+        double xs[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) xs[s] = ((valid >> s) & 1) ? (double)Xp[(size_t)sf[s] * ld + kk] : 0.0;
+        sigma += wk * xi * xi;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            double ws = wk * xs[s];
+            b[s] += ws * xi;
+#pragma unroll
+            for (int t = 0; t <= s; ++t) G[s][t] += ws * xs[t];
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int t = s + 1; t < 4; ++t) G[s][t] = G[t][s];
+    // greedy selection (Algorithm 2)
+    int J = 0, nsel = 0;
+    double L[4][4], z[4], detJ = 1.0;
+#pragma unroll
+    for (int step = 0; step < 4; ++step) {
+        if (nsel >= caliber) break;
+        int best = -1;
+        double bestL = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (!((valid >> c) & 1) || ((J >> c) & 1)) continue;
+            int S = J | (1 << c);
+            double det;
+            bool ok = chol4(G, b, S, L, z, det);
+            if (!ok || !(det > 1e-10 * G[c][c] * detJ)) continue;
+            double Lv = sigma;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) Lv -= z[s] * z[s];
+            if (best < 0 || Lv < bestL) { best = c; bestL = Lv; }
+        }
+        if (best < 0) break;
+        J |= 1 << best;
+        ++nsel;
+        double det;
+        chol4(G, b, J, L, z, det);
+        detJ = det;
+    }
+    double p[4] = {0, 0, 0, 0};
+    if (J == 0) {
+        J = 1;
+        p[0] = 1.0;
+    } else {
+        double det;
+        chol4(G, b, J, L, z, det);
+        // back substitution L^T p = z on J
+#pragma unroll
+        for (int j = 3; j >= 0; --j) {
+            if (!((J >> j) & 1)) continue;
+            double s = z[j];
+#pragma unroll
+            for (int k = j + 1; k < 4; ++k) s -= L[k][j] * p[k];
+            p[j] = s / L[j][j];
+        }
+    }
+    // write the used slots in ascending coarse column (rank of each slot)
+    int cnt = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) cnt += (J >> s) & 1;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        if (!((J >> s) & 1)) continue;
+        int rank = 0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (((J >> t) & 1) && (sc[t] < sc[s])) ++rank;
+        pc[(size_t)i * 4 + rank] = sc[s];
+        pv[(size_t)i * 4 + rank] = (MP)p[s];
+    }
+    for (int s = cnt; s < 4; ++s) { pc[(size_t)i * 4 + s] = -1; pv[(size_t)i * 4 + s] = (MP)0; }
+    if (jmask) jmask[i] = J;
+}
+
+// ---------------------------------------------------------------- Q
+// Averaging restriction (Section 4): Q[I, i] = 1/|J_i| for every fine i with
+// I in J_i.  Such i lie in the 3x3 fine box around I's fine position; they
+// are written in ascending fine index.
+template <typename MQ>
+__global__ void k_build_q(int nc, GridDev g, FastDiv dcy, int ncy, const int* __restrict__ pc,
+                          int* __restrict__ qc, MQ* __restrict__ qv) {
+    int I = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (I >= nc) return;
+    int A = (int)dcy.div((uint32_t)I), Bq = I - A * ncy;
+    int fa = 2 * A, fb = 2 * Bq;
+    int fi[9];
+    double fv[9];
+#pragma unroll
+    for (int s = 0; s < 9; ++s) {
+        int da = s / 3 - 1, db = s % 3 - 1;
+        int na = fa + da, nb = fb + db;
+        fi[s] = -1; fv[s] = 0.0;
+        if (g.periodic) {
+            na = na < 0 ? na + g.nx : (na >= g.nx ? na - g.nx : na);
+            nb = nb < 0 ? nb + g.ny : (nb >= g.ny ? nb - g.ny : nb);
+        } else if (na < 0 || na >= g.nx || nb < 0 || nb >= g.ny) {
+            continue;
+        }
+        int i = na * g.ny + nb;
+        int c = 0;
+        bool hit = false;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            int J = pc[(size_t)i * 4 + t];
+            c += J >= 0;
+            hit |= J == I;
+        }
+        if (hit) { fi[s] = i; fv[s] = 1.0 / c; }
+    }
+    int cnt = 0;
+#pragma unroll
+    for (int s = 0; s < 9; ++s) cnt += fi[s] >= 0;
+#pragma unroll
+    for (int s = 0; s < 9; ++s) {
+        if (fi[s] < 0) continue;
+        int rank = 0;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) rank += (fi[t] >= 0) && (fi[t] < fi[s]);
+        qc[(size_t)I * 9 + rank] = fi[s];
+        qv[(size_t)I * 9 + rank] = (MQ)fv[s];
+    }
+    for (int s = cnt; s < 9; ++s) { qc[(size_t)I * 9 + s] = -1; qv[(size_t)I * 9 + s] = (MQ)0; }
+}
+
+// ---------------------------------------------------------------- Galerkin
+// Slot (0..8) of coarse column J in the 3x3 coarse box around coarse row I.
+__device__ __forceinline__ int box_slot(int I_a, int I_b, int J, const FastDiv& dcy, int ncx, int ncy, int periodic) {
+    int Ja = (int)dcy.div((uint32_t)J), Jb = J - Ja * ncy;
+    int da = grid_delta(I_a, Ja, ncx, periodic), db = grid_delta(I_b, Jb, ncy, periodic);
+    return (da + 1) * 3 + (db + 1);
+}
+
+// Symbolic pass of Q (M P): 9-bit mask of the coarse box slots reached by row
+// I (every coarse stencil lies in that box: Q, M and P each reach one grid
+// step).  cnt[I] = number of distinct columns.  M == identity when mrp is null.
+__global__ void k_galerkin_symbolic(int nc, FastDiv dcy, int ncx, int ncy, int periodic,
+                                    const int* __restrict__ qc, const int* __restrict__ mrp,
+                                    const int* __restrict__ mci, const int* __restrict__ pc,
+                                    int* __restrict__ cnt, unsigned short* __restrict__ mask_out) {
+    int I = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (I >= nc) return;
+    int Ia = (int)dcy.div((uint32_t)I), Ib = I - Ia * ncy;
+    unsigned mask = 0;
+    for (int s = 0; s < 9; ++s) {
+        int i = qc[(size_t)I * 9 + s];
+        if (i < 0) break;
+        int p0 = mrp ? mrp[i] : 0, p1 = mrp ? mrp[i + 1] : 1;
+        for (int p = p0; p < p1; ++p) {
+            int j = mrp ? mci[p] : i;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                int J = pc[(size_t)j * 4 + t];
+                if (J >= 0) mask |= 1u << box_slot(Ia, Ib, J, dcy, ncx, ncy, periodic);
+            }
+        }
+    }
+    // columns of distinct slots are distinct (coarse sides >= 3)
+    cnt[I] = __popc(mask);
+    mask_out[I] = (unsigned short)mask;
+}
+
+// Numeric pass: row I of Q (M P) accumulated as sum_i q_Ii (sum_j m_ij p_jJ)
+// in Q-row order, M-row order and P-row order (fixed order), written in
+// ascending coarse column at crp[I].
+template <typename MV>
+__global__ void __launch_bounds__(BAMG_BLK)
+k_galerkin_numeric(int nc, FastDiv dcy, int ncx, int ncy, int periodic,
+                   const int* __restrict__ qc, const MV* __restrict__ qv,
+                   const int* __restrict__ mrp, const int* __restrict__ mci, const MV* __restrict__ mv,
+                   const int* __restrict__ pc, const MV* __restrict__ pv,
+                   const unsigned short* __restrict__ mask_in, const int* __restrict__ crp,
+                   int* __restrict__ cci, MV* __restrict__ cv) {
+    int I = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (I >= nc) return;
+    int Ia = (int)dcy.div((uint32_t)I), Ib = I - Ia * ncy;
+    MV acc[9];
+#pragma unroll
+    for (int s = 0; s < 9; ++s) acc[s] = 0;
+    for (int s = 0; s < 9; ++s) {
+        int i = qc[(size_t)I * 9 + s];
+        if (i < 0) break;
+        MV q = qv[(size_t)I * 9 + s];
+        MV tmp[9];
+#pragma unroll
+        for (int u = 0; u < 9; ++u) tmp[u] = 0;
+        int p0 = mrp ? mrp[i] : 0, p1 = mrp ? mrp[i + 1] : 1;
+        for (int p = p0; p < p1; ++p) {
+            int j = mrp ? mci[p] : i;
+            MV m = mrp ? mv[p] : (MV)1;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                int J = pc[(size_t)j * 4 + t];
+                if (J < 0) continue;
+                int sl = box_slot(Ia, Ib, J, dcy, ncx, ncy, periodic);
+                MV c = m * pv[(size_t)j * 4 + t];
+#pragma unroll
+                for (int u = 0; u < 9; ++u) tmp[u] += (u == sl) ? c : (MV)0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 9; ++u) acc[u] += q * tmp[u];
+    }
+    unsigned mask = mask_in[I];
+    int base = crp[I];
+    // column of each slot, then rank among the active slots
+    int col[9];
+#pragma unroll
+    for (int u = 0; u < 9; ++u) {
+        int a = Ia + u / 3 - 1, b = Ib + u % 3 - 1;
+        if (periodic) {
+            a = a < 0 ? a + ncx : (a >= ncx ? a - ncx : a);
+            b = b < 0 ? b + ncy : (b >= ncy ? b - ncy : b);
+        }
+        col[u] = a * ncy + b;
+    }
+#pragma unroll
+    for (int u = 0; u < 9; ++u) {
+        if (!((mask >> u) & 1)) continue;
+        int rank = 0;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) rank += ((mask >> t) & 1) && (col[t] < col[u]);
+        cci[base + rank] = col[u];
+        cv[base + rank] = acc[u];
+    }
+}
+
+// ---------------------------------------------------------------- up-leg
+// One omega-Jacobi sweep on (B - lam_c T) x_c = 0 for every column c of the
+// eigenvector block V (R columns, row-major).  kind[c]: 0 real column with
+// real lam, 1/2 real/imaginary part of a complex pair (x = V_c + i V_{c+1},
+// lam complex); D_lam = diag(B) - lam diag(T).  T == identity when trp is
+// null.  Column 0 (the null-vector approximation) has lam = 0.
+template <typename T, typename M>
+__global__ void __launch_bounds__(BAMG_BLK)
+k_eig_relax(int n, int R, const int* __restrict__ brp, const int* __restrict__ bci, const M* __restrict__ bv,
+            const int* __restrict__ trp, const int* __restrict__ tci, const M* __restrict__ tv,
+            const double* __restrict__ lam, const int* __restrict__ kind, double omega,
+            const T* __restrict__ X, T* __restrict__ Y) {
+    int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    double bx[10], tx[10], bd = 0, td = trp ? 0.0 : 1.0;
+    for (int c = 0; c < R; ++c) { bx[c] = 0; tx[c] = trp ? 0.0 : (double)X[(size_t)i * R + c]; }
+    for (int p = brp[i]; p < brp[i + 1]; ++p) {
+        int j = bci[p];
+        double b = (double)bv[p];
+        if (j == i) bd = b;
+        for (int c = 0; c < R; ++c) bx[c] += b * (double)X[(size_t)j * R + c];
+    }
+    if (trp)
+        for (int p = trp[i]; p < trp[i + 1]; ++p) {
+            int j = tci[p];
+            double t = (double)tv[p];
+            if (j == i) td = t;
+            for (int c = 0; c < R; ++c) tx[c] += t * (double)X[(size_t)j * R + c];
+        }
+    for (int c = 0; c < R; ++c) {
+        int k = kind[c];
+        double lr = lam[2 * c], li = lam[2 * c + 1];
+        if (k == 0) {
+            double res = bx[c] - lr * tx[c];
+            double d = bd - lr * td;
+            Y[(size_t)i * R + c] = (T)((double)X[(size_t)i * R + c] - omega * res / d);
+        } else if (k == 1) {
+            // x = a + i b, r = (B - lam T) x, D = bd - lam td
+            double rr = (bx[c] - lr * tx[c]) + li * tx[c + 1];
+            double ri = (bx[c + 1] - lr * tx[c + 1]) - li * tx[c];
+            double dr = bd - lr * td, di = -li * td;
+            double den = dr * dr + di * di;
+            double qr = (rr * dr + ri * di) / den, qi = (ri * dr - rr * di) / den;
+            Y[(size_t)i * R + c] = (T)((double)X[(size_t)i * R + c] - omega * qr);
+            Y[(size_t)i * R + c + 1] = (T)((double)X[(size_t)i * R + c + 1] - omega * qi);
+            ++c;
+        }
+    }
+}
+
+// Rayleigh quotient partials for column pair/real column c: x^H B x and
+// x^H T x (re, im) -> part[block][entry][4].  ent_col: first column of entry e.
+template <typename T, typename M>
+__global__ void k_rayleigh_partial(int n, int R, int nent, const int* __restrict__ ent_col,
+                                   const int* __restrict__ kind,
+                                   const int* __restrict__ brp, const int* __restrict__ bci, const M* __restrict__ bv,
+                                   const int* __restrict__ trp, const int* __restrict__ tci, const M* __restrict__ tv,
+                                   const T* __restrict__ X, double* __restrict__ part) {
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    for (int e = 0; e < nent; ++e) {
+        int c = ent_col[e];
+        bool pair = kind[c] == 1;
+        double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < n; i += gridDim.x * BAMG_BLK) {
+            double xr = (double)X[(size_t)i * R + c], xi = pair ? (double)X[(size_t)i * R + c + 1] : 0.0;
+            double br = 0, bi = 0, tr = 0, ti = 0;
+            for (int p = brp[i]; p < brp[i + 1]; ++p) {
+                int j = bci[p];
+                double b = (double)bv[p];
+                br += b * (double)X[(size_t)j * R + c];
+                if (pair) bi += b * (double)X[(size_t)j * R + c + 1];
+            }
+            if (trp) {
+                for (int p = trp[i]; p < trp[i + 1]; ++p) {
+                    int j = tci[p];
+                    double t = (double)tv[p];
+                    tr += t * (double)X[(size_t)j * R + c];
+                    if (pair) ti += t * (double)X[(size_t)j * R + c + 1];
+                }
+            } else {
+                tr = xr; ti = xi;
+            }
+            // conj(x) * y = (xr - i xi)(yr + i yi)
+            s0 += xr * br + xi * bi; s1 += xr * bi - xi * br;
+            s2 += xr * tr + xi * ti; s3 += xr * ti - xi * tr;
+        }
+        s0 = block_sum(s0, sh); s1 = block_sum(s1, sh); s2 = block_sum(s2, sh); s3 = block_sum(s3, sh);
+        if (threadIdx.x == 0) {
+            double* o = part + ((size_t)blockIdx.x * nent + e) * 4;
+            o[0] = s0; o[1] = s1; o[2] = s2; o[3] = s3;
+        }
+    }
+}
+
+// lam_e = (x^H B x) / (x^H T x) for every entry except the null vector
+// (entry 0 keeps lam = 0); real columns keep a real lam.
+__global__ void k_rayleigh_final(int nparts, int nent, const int* __restrict__ ent_col, const int* __restrict__ kind,
+                                 const double* __restrict__ part, double* __restrict__ lam) {
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    int e = blockIdx.x;
+    double s[4] = {0, 0, 0, 0};
+    for (int j = threadIdx.x; j < nparts; j += BAMG_BLK)
+        for (int q = 0; q < 4; ++q) s[q] += part[((size_t)j * nent + e) * 4 + q];
+    for (int q = 0; q < 4; ++q) s[q] = block_sum(s[q], sh);
+    if (threadIdx.x == 0 && e > 0) {
+        int c = ent_col[e];
+        double den = s[2] * s[2] + s[3] * s[3];
+        double lr = (s[0] * s[2] + s[1] * s[3]) / den, li = (s[1] * s[2] - s[0] * s[3]) / den;
+        if (kind[c] == 0) li = 0.0;
+        lam[2 * c] = lr; lam[2 * c + 1] = li;
+        if (kind[c] == 1) { lam[2 * c + 2] = lr; lam[2 * c + 3] = li; }
+    }
+}
+
+// ---------------------------------------------------------------- casts
+template <typename A, typename B>
+__global__ void k_cast(long long n, const A* __restrict__ a, B* __restrict__ b) {
+    long long i = (long long)blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i < n) b[i] = (B)a[i];
+}
+
+// Initial test vectors U[i*r + k] = u(seed, stream 1, i*r + k).
+template <typename T>
+__global__ void k_tv_init(long long total, uint64_t seed, T* __restrict__ U) {
+    long long t = (long long)blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (t < total) U[t] = (T)splitmix_u01(seed, 1ull, (uint64_t)t);
+}

@@ -1,0 +1,41 @@
+"""The C-ABI library loads on a machine without a GPU and exports every
+function include/bamg.h declares; host-side defaults match the header."""
+import os
+import re
+
+from paper_1004_1451_amd import bamg as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "bamg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bamg_[a-z_]+)\s*\(", src)))
+
+
+def test_header_functions_are_exported():
+    lib = B.load()
+    names = _declared()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(B.EXPORTS) == names
+
+
+def test_default_options():
+    o = B.default_options()
+    assert (o.levels, o.coarse_max, o.nu_setup, o.nu_pre, o.nu_post) == (0, 1024, 4, 2, 2)
+    assert o.omega == 0.7 and o.caliber == 4 and o.n_eig == 6 and o.gmres_m == 50
+    assert o.precision == B.FP64 and o.interp == B.INTERP_LS
+
+
+def test_null_arguments_fail_without_gpu():
+    import ctypes as C
+    lib = B.load()
+    h = C.c_void_p()
+    rc = lib.bamg_setup(4, None, None, None, B.Grid(2, 2, 0), 1, None, None, C.byref(h))
+    assert rc == B.EINVAL
+    assert b"NULL" in lib.bamg_last_error()
+    assert lib.bamg_free(None) == B.OK
+    assert lib.bamg_solve(None, None, 1e-10, 1, 0, None) == B.EINVAL
