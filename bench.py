@@ -1,0 +1,165 @@
+"""Benchmark: setup + solve seconds to ||Bx||_1/||x||_1 <= 1e-10 on the
+n = 4,194,304 tandem queue (N = 2047, r = 12 test vectors, 6 levels), one
+MI355X.  Prints one JSON line.
+
+A step is one whole pass of the method over the resident input: bamg_setup
+(relaxation, LS interpolation, Galerkin products, coarsest eigensolve,
+up-leg, recomputation) + bamg_solve (V-cycle-preconditioned FGMRES to the
+tolerance) + bamg_free.  The roofline object reports the level-0 test-vector
+sweep: algorithmic bytes per launch / mean launch time (HIP events recorded
+by the library on its own stream during the timed steps).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def _traffic_from_profiles(kernel: str):
+    """HBM bytes per launch measured by rocprofv3 counters, if a summary for
+    this kernel is committed (profiles/<kernel>_traffic.txt: a line
+    'bytes_per_launch: <value>' and 'source_hash: <sha>'), else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    import hashlib
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_1004_1451_amd", "csrc", "k_sparse.h")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if vals.get("source_hash") != h:
+        return None          # kernel changed since the counters were taken
+    try:
+        return float(vals["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(args):
+    """The oracle, untuned, on a bounded sample: the whole method on the
+    tandem queue N = 255 (n = 65,536; 4 levels; same r, rates and tolerance),
+    scaled to n = 4,194,304 by the ratio of state counts (the work per level
+    is linear in n).  BLAS limited to one thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle import bamg_oracle as O
+    from paper_1004_1451_amd import chains as C
+    ch = C.tandem_queue(255)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        x, info, _ = O.stationary(ch.to_scipy(), O.Grid(ch.nx, ch.ny, ch.periodic), args.r,
+                                  O.Options(levels=4), tol=args.tol, max_cycles=200)
+        dt = time.perf_counter() - t0
+    scale = 4194304 / ch.n
+    return {"value": dt * scale, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle setup+solve on tandem N=255 (n={ch.n}, 4 levels, r={args.r}, tol={args.tol:g}) "
+                      f"took {dt:.2f} s on 1 thread; scaled by n ratio {scale:.0f}",
+            "converged": bool(info.converged)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--N", type=int, default=2047, help="tandem queue capacity (side N+1)")
+    ap.add_argument("--levels", type=int, default=6)
+    ap.add_argument("--r", type=int, default=12)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is described "
+              f"in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1004_1451_amd import bamg as B
+    from paper_1004_1451_amd import chains as C
+
+    ch = C.tandem_queue(args.N)
+    rp, ci, v = B.device_csr(ch)
+    x = torch.empty(ch.n, dtype=torch.float64, device="cuda")
+    prec = B.FP64 if args.precision == "fp64" else B.MIXED
+    opts = B.default_options(levels=args.levels, precision=prec, profile=1)
+
+    def step():
+        h = B.Hierarchy(ch.n, rp, ci, v, (ch.nx, ch.ny, 0), args.r, opts)
+        info = h.solve(x, args.tol, 200)
+        st = h.stats()
+        h.close()
+        return info, st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    infos, stats = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        info, st = step()
+        infos.append(info)
+        stats.append(st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sec = dt / args.steps
+
+    sweep_ms = sum(s.sweep_ms for s in stats) / max(1, sum(s.sweep_launches for s in stats))
+    sweep_bytes = stats[-1].sweep_bytes
+    achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9
+    gal_ms = sum(s.galerkin_ms for s in stats) / max(1, sum(s.galerkin_launches for s in stats))
+    ls_ms = sum(s.lsfit_ms for s in stats) / max(1, sum(s.lsfit_launches for s in stats))
+    traffic = _traffic_from_profiles("k_sweep")
+    out = {
+        "metric": "setup+solve seconds to ||Bx||_1/||x||_1<=1e-10 at n=4.2M; sweep HBM GB/s",
+        "value": round(sec, 6),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == B.FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"tandem queue N={args.N} (n={ch.n:,}), rates 11/31,10/31,10/31, r={args.r}, "
+                               f"{args.levels} levels, tol {args.tol:g}",
+                   "precision": args.precision},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "kernel": "k_sweep (level-0 test-vector sweep, R=%d)" % args.r,
+                     "bytes_per_launch": int(sweep_bytes), "mean_launch_us": round(sweep_ms * 1e3, 2)},
+        "detail": {
+            "setup_ms": round(float(np.mean([s.t_setup_ms for s in stats])), 3),
+            "solve_ms": round(float(np.mean([s.t_solve_ms for s in stats])), 3),
+            "cycles": [i.cycles for i in infos],
+            "residual_l1": max(i.residual_l1 for i in infos),
+            "converged": all(i.converged for i in infos),
+            "op_complexity": round(stats[-1].op_complexity, 4),
+            "galerkin_numeric_us": round(gal_ms * 1e3, 2),
+            "galerkin_GBps": round(stats[-1].galerkin_bytes / (gal_ms * 1e-3) / 1e9, 1) if gal_ms > 0 else None,
+            "lsfit_us": round(ls_ms * 1e3, 2),
+            "lsfit_GBps": round(stats[-1].lsfit_bytes / (ls_ms * 1e-3) / 1e9, 1) if ls_ms > 0 else None,
+            "coarsest_min_pivot": stats[-1].coarsest_min_pivot,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

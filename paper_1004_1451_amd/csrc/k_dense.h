@@ -60,6 +60,7 @@ k_gj_diag(int ld, int k0, int nb, double* __restrict__ A, const double* __restri
           double* __restrict__ minpiv) {
     __shared__ double S[GJ_NB][GJ_NB + 1];
     __shared__ double prow[GJ_NB + 1];
+    __shared__ double pcol[GJ_NB + 1];
     const int tid = threadIdx.x;
     for (int e = tid; e < nb * nb; e += BAMG_BLK) {
         int r = e / nb, c = e % nb;
@@ -71,13 +72,17 @@ k_gj_diag(int ld, int k0, int nb, double* __restrict__ A, const double* __restri
         double piv = S[k][k];
         if (tid == 0) mp = fmin(mp, fabs(piv) / *scale);
         double ip = 1.0 / piv;
-        // scaled pivot row (column k becomes 1/piv)
-        if (tid < nb) prow[tid] = (tid == k) ? ip : S[k][tid] * ip;
+        // scaled pivot row (column k becomes 1/piv) and a snapshot of the
+        // pivot column: the update below overwrites column k
+        if (tid < nb) {
+            prow[tid] = (tid == k) ? ip : S[k][tid] * ip;
+            pcol[tid] = S[tid][k];
+        }
         __syncthreads();
         for (int e = tid; e < nb * nb; e += BAMG_BLK) {
             int r = e / nb, c = e % nb;
             if (r == k) continue;
-            double f = S[r][k];
+            double f = pcol[r];
             S[r][c] = (c == k) ? -f * ip : S[r][c] - f * prow[c];
         }
         __syncthreads();
