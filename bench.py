@@ -146,6 +146,7 @@ def main():
             "setup_ms": round(float(np.mean([s.t_setup_ms for s in stats])), 3),
             "solve_ms": round(float(np.mean([s.t_solve_ms for s in stats])), 3),
             "cycles": [i.cycles for i in infos],
+            "history": [float("%.3e" % v) for v in list(infos[-1].history)[: infos[-1].history_len]],
             "residual_l1": max(i.residual_l1 for i in infos),
             "converged": all(i.converged for i in infos),
             "op_complexity": round(stats[-1].op_complexity, 4),

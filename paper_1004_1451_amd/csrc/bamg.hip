@@ -55,6 +55,7 @@ struct BamgError : std::runtime_error {
 
 inline int nblk(long long n) { return (int)std::max<long long>(1, (n + BAMG_BLK - 1) / BAMG_BLK); }
 constexpr int RED_PARTS = 1024;       // fixed partition of every FP64 reduction
+constexpr int MDOT_BLOCKS = 1024;     // fixed row partition of the GMRES multi-dots
 
 struct GridH {
     int nx, ny, periodic;
@@ -309,7 +310,12 @@ struct Engine : bamg_ctx {
         kind = A.alloc<int>(16);
         ent_col = A.alloc<int>(16);
         x0 = A.alloc<double>(n);
-        part = A.alloc<double>((size_t)RED_PARTS * 2 * 64 + 4096);
+        {
+            size_t need = std::max<size_t>((size_t)RED_PARTS * 2 * 64 + 4096,
+                                           (size_t)MDOT_BLOCKS * (BAMG_BLK / BAMG_WAVE) * (o.gmres_m + 2));
+            need = std::max<size_t>(need, (size_t)ceil_div(nL, GT_ROWS) * nL);
+            part = A.alloc<double>(need);
+        }
         sc = A.alloc<double>(64);
         wts = A.alloc<double>(64);
         err = A.alloc<int>(4);
@@ -395,12 +401,13 @@ struct Engine : bamg_ctx {
             Csr<T>& M = which == 0 ? f.B : f.Tm;
             Csr<T>& C = which == 0 ? c.B : c.Tm;
             const int* mrp = M.rp;
-            LAUNCH(k_galerkin_symbolic, nblk(nc), BAMG_BLK, s, nc, dcy, cg.nx, cg.ny, cg.periodic, f.qc, mrp, M.ci,
+            const int gb = ceil_div(nc, GAL_ROWS);
+            LAUNCH(k_galerkin_symbolic, gb, GAL_THREADS, s, nc, dcy, cg.nx, cg.ny, cg.periodic, f.qc, mrp, M.ci,
                    f.pc, f.cnt, f.mask);
             scan(nc, f.cnt, C.rp);
             std::pair<hipEvent_t, hipEvent_t> ev;
             if (profile) ev = ev_begin();
-            LAUNCH(k_galerkin_numeric<T>, nblk(nc), BAMG_BLK, s, nc, dcy, cg.nx, cg.ny, cg.periodic, f.qc,
+            LAUNCH(k_galerkin_numeric<T>, gb, GAL_THREADS, s, nc, dcy, cg.nx, cg.ny, cg.periodic, f.qc,
                    (const T*)f.qv, mrp, M.ci, (const T*)M.v, f.pc, (const T*)f.pv, f.mask, C.rp, C.ci, C.v);
             if (profile) ev_end(ev, ev_gal);
         }
@@ -436,11 +443,12 @@ struct Engine : bamg_ctx {
         HIPCHK(hipMemcpyAsync(sc + 11, &big, sizeof(double), hipMemcpyHostToDevice, s));
         if (m > 0) {
             const int tiles = ceil_div(m, 64);
+            const int ut = ceil_div(m, GJ_T);
             for (int k0 = 0; k0 < m; k0 += GJ_NB) {
                 int nb = std::min(GJ_NB, m - k0);
                 LAUNCH(k_gj_diag, 1, BAMG_BLK, s, nL, k0, nb, W, (const double*)(sc + 10), sc + 11);
                 LAUNCH(k_gj_rowpanel, tiles, BAMG_BLK, s, m, nL, k0, nb, W);
-                LAUNCH(k_gj_update, tiles * tiles, BAMG_BLK, s, m, nL, k0, nb, W);
+                LAUNCH(k_gj_update, ut * ut, BAMG_BLK, s, m, nL, k0, nb, W);
                 LAUNCH(k_gj_colpanel, tiles, BAMG_BLK, s, m, nL, k0, nb, W);
             }
         }
@@ -451,7 +459,13 @@ struct Engine : bamg_ctx {
         // projections: s = W 1, u = y^T W, sc0 = y^T s, sc1 = y^T y
         LAUNCH(k_fill, nblk(nL), BAMG_BLK, s, (long long)nL, 1.0, tmpL2);
         LAUNCH(k_gemv, ceil_div(nL, 4), BAMG_BLK, s, nL, nL, nL, (const double*)W, (const double*)tmpL2, tmpL);
-        LAUNCH(k_gemv_t, nblk(nL), BAMG_BLK, s, nL, nL, nL, (const double*)W, (const double*)y, tmpL2);
+        {
+            dim3 gt(nblk(nL), ceil_div(nL, GT_ROWS));
+            hipLaunchKernelGGL(k_gemv_t_partial, gt, dim3(BAMG_BLK), 0, s, nL, nL, nL, (const double*)W,
+                               (const double*)y, part);
+            HIPCHK(hipGetLastError());
+            LAUNCH(k_gemv_t_final, nblk(nL), BAMG_BLK, s, (int)gt.y, nL, (const double*)part, tmpL2);
+        }
         LAUNCH(k_dot1, 1, BAMG_BLK, s, nL, (const double*)y, (const double*)tmpL, sc + 0);
         LAUNCH(k_dot1, 1, BAMG_BLK, s, nL, (const double*)y, (const double*)y, sc + 1);
         LAUNCH(k_project_w, nblk(nn), BAMG_BLK, s, nL, W, (const double*)tmpL, (const double*)tmpL2, (const double*)y,
@@ -763,8 +777,10 @@ struct Engine : bamg_ctx {
                 LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)zj, 1.0, wk);
                 double* hcol = Hg + (size_t)j * (m + 1);
                 for (int pass = 0; pass < 2; ++pass) {
-                    LAUNCH(k_mdot_partial, 256, BAMG_BLK, s, N, j + 1, (const double*)Vk, (const double*)wk, part);
-                    LAUNCH(k_mdot_final, j + 1, BAMG_BLK, s, 256, j + 1, (const double*)part, hbuf, hcol);
+                    LAUNCH(k_mdot_partial, MDOT_BLOCKS, BAMG_BLK, s, N, j + 1, (const double*)Vk, (const double*)wk,
+                           part);
+                    LAUNCH(k_mdot_final, j + 1, BAMG_BLK, s, MDOT_BLOCKS * (BAMG_BLK / BAMG_WAVE), j + 1,
+                           (const double*)part, hbuf, hcol);
                     LAUNCH(k_vupdate, nb, BAMG_BLK, s, N, j + 1, (const double*)Vk, (const double*)hbuf, wk);
                 }
                 reduce<RED_DOT>(N, wk, wk, sc + 24);
@@ -957,7 +973,7 @@ int bamg_setup(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const 
             fail(BAMG_EINVAL, "invalid options");
         if (o.interp != BAMG_INTERP_LS) fail(BAMG_EUNSUPPORTED, "interpolation mode %d not available", o.interp);
         if (o.precision == BAMG_FP64) ctx = new Engine<double>();
-        else if (o.precision == BAMG_MIXED) fail(BAMG_EUNSUPPORTED, "mixed precision not available in this build");
+        else if (o.precision == BAMG_MIXED) ctx = new Engine<float>();
         else fail(BAMG_EINVAL, "unknown precision %d", o.precision);
         ctx->s = (hipStream_t)stream;
         ctx->o = o;

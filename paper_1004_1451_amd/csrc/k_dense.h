@@ -53,46 +53,70 @@ __global__ void k_absmax_partial(long long n, const double* __restrict__ a, doub
 }
 
 // In-place inverse of the diagonal block A[k0:k0+nb, k0:k0+nb] (ld) by
-// Gauss-Jordan without pivoting, in LDS.  Records min |pivot| / scale in
-// *minpiv (scale = max |B_L| entry; a single block runs this kernel).
+// Gauss-Jordan without pivoting.  The block (padded to 64 x 64 with an
+// identity) lives in registers: thread t owns the 4 x 4 sub-block at rows
+// 4*(t/16), columns 4*(t%16).  Each step publishes the pivot row and column
+// in LDS (double-buffered, one barrier per step).  Records min |pivot| /
+// scale in *minpiv (scale = max |B_L| entry; one block runs this kernel).
 __global__ void __launch_bounds__(BAMG_BLK)
 k_gj_diag(int ld, int k0, int nb, double* __restrict__ A, const double* __restrict__ scale,
           double* __restrict__ minpiv) {
-    __shared__ double S[GJ_NB][GJ_NB + 1];
-    __shared__ double prow[GJ_NB + 1];
-    __shared__ double pcol[GJ_NB + 1];
+    __shared__ double prow[2][GJ_NB], pcol[2][GJ_NB];
     const int tid = threadIdx.x;
-    for (int e = tid; e < nb * nb; e += BAMG_BLK) {
-        int r = e / nb, c = e % nb;
-        S[r][c] = A[(size_t)(k0 + r) * ld + k0 + c];
-    }
-    __syncthreads();
+    const int r0 = (tid / 16) * 4, c0 = (tid % 16) * 4;
+    double S[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            int r = r0 + a, c = c0 + b;
+            S[a][b] = (r < nb && c < nb) ? A[(size_t)(k0 + r) * ld + k0 + c] : (r == c ? 1.0 : 0.0);
+        }
+    const double sc = *scale;
     double mp = 1e300;
-    for (int k = 0; k < nb; ++k) {
-        double piv = S[k][k];
-        if (tid == 0) mp = fmin(mp, fabs(piv) / *scale);
-        double ip = 1.0 / piv;
-        // scaled pivot row (column k becomes 1/piv) and a snapshot of the
-        // pivot column: the update below overwrites column k
-        if (tid < nb) {
-            prow[tid] = (tid == k) ? ip : S[k][tid] * ip;
-            pcol[tid] = S[tid][k];
+    for (int k = 0; k < GJ_NB; ++k) {
+        const int buf = k & 1;
+        // publish pivot row k and pivot column k (before this step's update)
+        if (k >= r0 && k < r0 + 4) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+                if (r0 + a == k)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) prow[buf][c0 + b] = S[a][b];
+        }
+        if (k >= c0 && k < c0 + 4) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (c0 + b == k)
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) pcol[buf][r0 + a] = S[a][b];
         }
         __syncthreads();
-        for (int e = tid; e < nb * nb; e += BAMG_BLK) {
-            int r = e / nb, c = e % nb;
-            if (r == k) continue;
-            double f = pcol[r];
-            S[r][c] = (c == k) ? -f * ip : S[r][c] - f * prow[c];
+        const double piv = prow[buf][k];
+        if (tid == 0 && k < nb) mp = fmin(mp, fabs(piv) / sc);
+        const double ip = 1.0 / piv;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int r = r0 + a;
+            const double f = pcol[buf][r];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int c = c0 + b;
+                const double pr = prow[buf][c];
+                double v;
+                if (r == k) v = (c == k) ? ip : pr * ip;
+                else v = (c == k) ? -f * ip : S[a][b] - f * (pr * ip);
+                S[a][b] = v;
+            }
         }
-        __syncthreads();
-        if (tid < nb) S[k][tid] = prow[tid];
-        __syncthreads();
     }
-    for (int e = tid; e < nb * nb; e += BAMG_BLK) {
-        int r = e / nb, c = e % nb;
-        A[(size_t)(k0 + r) * ld + k0 + c] = S[r][c];
-    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            int r = r0 + a, c = c0 + b;
+            if (r < nb && c < nb) A[(size_t)(k0 + r) * ld + k0 + c] = S[a][b];
+        }
     if (tid == 0) *minpiv = fmin(*minpiv, mp);
 }
 
@@ -121,52 +145,56 @@ k_gj_rowpanel(int m, int ld, int k0, int nb, double* __restrict__ A) {
     }
 }
 
-// Rank-nb update of every block outside row block and column block k:
-// A[i, j] -= A[i, k-block] * A[k-block, j].  64 x 64 tiles, 4 x 4 per thread.
+// Rank-nb update of every entry outside row block and column block k:
+// A[i, j] -= A[i, k-block] * A[k-block, j].  128 x 128 output tiles, 8 x 8
+// per thread (256 threads), the k-block factors staged in LDS (A part
+// transposed so that both operands are read as contiguous 8-double runs).
+// Rows / columns inside the k-block are computed but not written.
+#define GJ_T 128
 __global__ void __launch_bounds__(BAMG_BLK)
 k_gj_update(int m, int ld, int k0, int nb, double* __restrict__ A) {
-    __shared__ double As[64][GJ_NB + 1];
-    __shared__ double Bs[GJ_NB][64 + 1];
-    const int tiles = ceil_div(m, 64);
+    __shared__ double AsT[GJ_NB][GJ_T + 2];
+    __shared__ double Bs[GJ_NB][GJ_T + 2];
+    const int tiles = ceil_div(m, GJ_T);
     int t = xcd_tile(blockIdx.x, gridDim.x);
     int ti = t / tiles, tj = t % tiles;
-    int i0 = ti * 64, j0 = tj * 64;
-    if (i0 == k0 || j0 == k0) return;
+    int i0 = ti * GJ_T, j0 = tj * GJ_T;
     const int tid = threadIdx.x;
-    for (int e = tid; e < 64 * nb; e += BAMG_BLK) {
-        int r = e / nb, c = e % nb;
-        As[r][c] = (i0 + r < m) ? A[(size_t)(i0 + r) * ld + k0 + c] : 0.0;
+    // A[i0 + r][k0 + c]  -> AsT[c][r];  A[k0 + r][j0 + c] -> Bs[r][c]
+    for (int e = tid; e < GJ_T * GJ_NB; e += BAMG_BLK) {
+        int r = e / GJ_NB, c = e % GJ_NB;
+        AsT[c][r] = (i0 + r < m && c < nb) ? A[(size_t)(i0 + r) * ld + k0 + c] : 0.0;
     }
-    for (int e = tid; e < nb * 64; e += BAMG_BLK) {
-        int r = e / 64, c = e % 64;
-        Bs[r][c] = (j0 + c < m) ? A[(size_t)(k0 + r) * ld + j0 + c] : 0.0;
+    for (int e = tid; e < GJ_NB * GJ_T; e += BAMG_BLK) {
+        int r = e / GJ_T, c = e % GJ_T;
+        Bs[r][c] = (j0 + c < m && r < nb) ? A[(size_t)(k0 + r) * ld + j0 + c] : 0.0;
     }
     __syncthreads();
-    const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
-    double acc[4][4];
+    const int tr = (tid / 16) * 8, tc = (tid % 16) * 8;
+    double acc[8][8];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 8; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0;
+        for (int b = 0; b < 8; ++b) acc[a][b] = 0;
     for (int k = 0; k < nb; ++k) {
-        double av[4], bv[4];
+        double av[8], bv[8];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) av[a] = As[tr + a][k];
+        for (int a = 0; a < 8; ++a) av[a] = AsT[k][tr + a];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) bv[b] = Bs[k][tc + b];
+        for (int b = 0; b < 8; ++b) bv[b] = Bs[k][tc + b];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 8; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+            for (int b = 0; b < 8; ++b) acc[a][b] += av[a] * bv[b];
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < 8; ++a) {
         int i = i0 + tr + a;
-        if (i >= m) continue;
+        if (i >= m || (i >= k0 && i < k0 + nb)) continue;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < 8; ++b) {
             int j = j0 + tc + b;
-            if (j < m) A[(size_t)i * ld + j] -= acc[a][b];
+            if (j < m && !(j >= k0 && j < k0 + nb)) A[(size_t)i * ld + j] -= acc[a][b];
         }
     }
 }
@@ -225,13 +253,25 @@ k_gemv_f32(int rows, int cols, int ld, const float* __restrict__ A, const float*
     if (lane == 0) y[row] = s;
 }
 
-// y^T A: column-weighted sums, one thread per column (coalesced rows).
-__global__ void k_gemv_t(int rows, int cols, int ld, const double* __restrict__ A, const double* __restrict__ y,
-                         double* __restrict__ out) {
+// y^T A in two stages: block (cx, ry) sums rows [ry*GT_ROWS, ...) of 256
+// columns into part[ry][col]; the second stage adds the row chunks in order.
+#define GT_ROWS 128
+__global__ void k_gemv_t_partial(int rows, int cols, int ld, const double* __restrict__ A,
+                                 const double* __restrict__ y, double* __restrict__ part) {
+    int j = blockIdx.x * BAMG_BLK + threadIdx.x;
+    int r0 = blockIdx.y * GT_ROWS;
+    if (j >= cols) return;
+    double s = 0;
+    int r1 = min(rows, r0 + GT_ROWS);
+    for (int i = r0; i < r1; ++i) s += y[i] * A[(size_t)i * ld + j];
+    part[(size_t)blockIdx.y * cols + j] = s;
+}
+
+__global__ void k_gemv_t_final(int nchunks, int cols, const double* __restrict__ part, double* __restrict__ out) {
     int j = blockIdx.x * BAMG_BLK + threadIdx.x;
     if (j >= cols) return;
     double s = 0;
-    for (int i = 0; i < rows; ++i) s += y[i] * A[(size_t)i * ld + j];
+    for (int c = 0; c < nchunks; ++c) s += part[(size_t)c * cols + j];
     out[j] = s;
 }
 

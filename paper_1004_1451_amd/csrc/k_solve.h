@@ -32,16 +32,21 @@ __global__ void k_reduce_final(int nparts, const double* __restrict__ part, doub
 }
 
 // Multi-dot h_b = <V_b, w> for b < nv (V: nv vectors of length n, stride n):
-// stage 1 over a fixed row partition -> part[block][nv].
-__global__ void k_mdot_partial(int n, int nv, const double* __restrict__ V, const double* __restrict__ w,
-                               double* __restrict__ part) {
-    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+// stage 1 over a fixed row partition; every wavefront writes its own partial
+// (no block barrier) -> part[(block*4 + wave)][nv].
+__global__ void __launch_bounds__(BAMG_BLK)
+k_mdot_partial(int n, int nv, const double* __restrict__ V, const double* __restrict__ w,
+               double* __restrict__ part) {
+    const int lane = threadIdx.x % BAMG_WAVE, wv = threadIdx.x / BAMG_WAVE;
+    const int chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int i0 = blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+    const size_t slot = ((size_t)blockIdx.x * (BAMG_BLK / BAMG_WAVE) + wv) * nv;
     for (int b = 0; b < nv; ++b) {
+        const double* vb = V + (size_t)b * n;
         double s = 0;
-        for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < n; i += gridDim.x * BAMG_BLK)
-            s += V[(size_t)b * n + i] * w[i];
-        s = block_sum(s, sh);
-        if (threadIdx.x == 0) part[(size_t)blockIdx.x * nv + b] = s;
+        for (int i = i0 + threadIdx.x; i < i1; i += BAMG_BLK) s += vb[i] * w[i];
+        s = wave_sum(s);
+        if (lane == 0) part[slot + b] = s;
     }
 }
 

@@ -161,6 +161,33 @@ __global__ void k_scan_add(int n, int* __restrict__ out, const int* __restrict__
 }
 
 // ---------------------------------------------------------------- relaxation
+
+// sum_p v[p] * X[ci[p]*R + k] over one CSR row, in CSR order.  Index and
+// value loads are issued four at a time before the dependent X loads, so a
+// row costs two memory round trips instead of two per entry; padding slots
+// add an exact zero, so the result equals the plain sequential sum.
+template <typename T, typename M>
+__device__ __forceinline__ T row_dot(int p0, int p1, const int* __restrict__ ci, const M* __restrict__ v,
+                                     const T* __restrict__ X, int R, int k, int self) {
+    T acc = 0;
+    for (int p = p0; p < p1; p += 4) {
+        int c[4];
+        M w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            bool ok = p + u < p1;
+            c[u] = ok ? ci[p + u] : self;
+            w[u] = ok ? v[p + u] : (M)0;
+        }
+        T x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = X[(size_t)c[u] * R + k];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += (T)w[u] * x[u];
+    }
+    return acc;
+}
+
 // X_out = X_in + dinv (F - B X_in) on R interleaved columns (omega-Jacobi,
 // Section 3).  One thread per (row, column); a wavefront covers 64/R rows and
 // every stencil offset reads a contiguous run of X.  F == nullptr: homogeneous.
@@ -172,11 +199,11 @@ k_sweep(int n, int R, FastDiv divR, const int* __restrict__ rp, const int* __res
     int t = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
     if (t >= n * R) return;
     int i = (int)divR.div((uint32_t)t), k = t - i * R;
-    int p0 = rp[i], p1 = rp[i + 1];
-    T acc = 0;
-    for (int p = p0; p < p1; ++p) acc += (T)v[p] * X[(size_t)ci[p] * R + k];
-    T r = (F ? F[t] : (T)0) - acc;
-    Y[t] = X[t] + (T)dinv[i] * r;
+    const T xt = X[t];
+    const T d = (T)dinv[i];
+    const T f = F ? F[t] : (T)0;
+    T acc = row_dot<T, M>(rp[i], rp[i + 1], ci, v, X, R, k, i);
+    Y[t] = xt + d * (f - acc);
 }
 
 // First smoothing sweep from a zero guess: e = dinv * f.
@@ -193,9 +220,9 @@ k_residual(int n, const int* __restrict__ rp, const int* __restrict__ ci, const 
            const T* __restrict__ e, const T* __restrict__ f, T* __restrict__ r) {
     int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
     if (i >= n) return;
-    T acc = 0;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) acc += (T)v[p] * e[ci[p]];
-    r[i] = (f ? f[i] : (T)0) - acc;
+    const T fi = f ? f[i] : (T)0;
+    T acc = row_dot<T, M>(rp[i], rp[i + 1], ci, v, e, 1, 0, i);
+    r[i] = fi - acc;
 }
 
 // y = alpha * B x with FP64 vectors (values widened), used by the outer
@@ -206,8 +233,7 @@ k_spmv(int n, const int* __restrict__ rp, const int* __restrict__ ci, const M* _
        const double* __restrict__ x, double alpha, double* __restrict__ y) {
     int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
     if (i >= n) return;
-    double acc = 0;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) acc += (double)v[p] * x[ci[p]];
+    double acc = row_dot<double, M>(rp[i], rp[i + 1], ci, v, x, 1, 0, i);
     y[i] = alpha * acc;
 }
 
@@ -420,21 +446,26 @@ k_ls_fit(int n, GridDev g, int ncy, int Ru, int Rv, const T* __restrict__ U, con
 #pragma unroll
         for (int t = 0; t < 4; ++t) G[s][t] = 0;
     }
-    for (int k = 0; k < Ru + Rv; ++k) {
-        const T* Xp = k < Ru ? U : V;
-        int ld = k < Ru ? Ru : Rv, kk = k < Ru ? k : k - Ru;
-        double wk = w[k];
-        double xi = (double)Xp[(size_t)i * ld + kk];
-        double xs[4];
+    // U columns, then V columns (test vectors in a fixed order k = 0..R-1)
+    for (int part = 0; part < 2; ++part) {
+        const T* Xp = part == 0 ? U : V;
+        const int ld = part == 0 ? Ru : Rv;
+        const double* wp = w + (part == 0 ? 0 : Ru);
+#pragma unroll 2
+        for (int kk = 0; kk < ld; ++kk) {
+            double wk = wp[kk];
+            double xi = (double)Xp[(size_t)i * ld + kk];
+            double xs[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) xs[s] = ((valid >> s) & 1) ? (double)Xp[(size_t)sf[s] * ld + kk] : 0.0;
-        sigma += wk * xi * xi;
+            for (int s = 0; s < 4; ++s) xs[s] = ((valid >> s) & 1) ? (double)Xp[(size_t)sf[s] * ld + kk] : 0.0;
+            sigma += wk * xi * xi;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            double ws = wk * xs[s];
-            b[s] += ws * xi;
+            for (int s = 0; s < 4; ++s) {
+                double ws = wk * xs[s];
+                b[s] += ws * xi;
 #pragma unroll
-            for (int t = 0; t <= s; ++t) G[s][t] += ws * xs[t];
+                for (int t = 0; t <= s; ++t) G[s][t] += ws * xs[t];
+            }
         }
     }
 #pragma unroll
@@ -561,98 +592,130 @@ __device__ __forceinline__ int box_slot(int I_a, int I_b, int J, const FastDiv& 
     return (da + 1) * 3 + (db + 1);
 }
 
-// Symbolic pass of Q (M P): 9-bit mask of the coarse box slots reached by row
-// I (every coarse stencil lies in that box: Q, M and P each reach one grid
-// step).  cnt[I] = number of distinct columns.  M == identity when mrp is null.
-__global__ void k_galerkin_symbolic(int nc, FastDiv dcy, int ncx, int ncy, int periodic,
-                                    const int* __restrict__ qc, const int* __restrict__ mrp,
-                                    const int* __restrict__ mci, const int* __restrict__ pc,
-                                    int* __restrict__ cnt, unsigned short* __restrict__ mask_out) {
-    int I = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
-    if (I >= nc) return;
-    int Ia = (int)dcy.div((uint32_t)I), Ib = I - Ia * ncy;
+// The Galerkin passes give each coarse row I nine threads, one per slot s of
+// Q row I (fine point i = qc[9I + s]); a block holds GAL_ROWS coarse rows.
+#define GAL_ROWS 28
+#define GAL_THREADS (9 * GAL_ROWS)
+
+// Contribution of Q slot s of coarse row I: the box slots reached through
+// i = qc[9I+s] (mask) and, with vals, tmp[u] = sum_j m_ij p_jJ (M-row order,
+// then P-row order) for J in box slot u.
+template <typename MV, bool VALS>
+__device__ __forceinline__ unsigned gal_slot(int I, int Ia, int Ib, int i, const FastDiv& dcy, int ncx, int ncy,
+                                             int periodic, const int* __restrict__ mrp, const int* __restrict__ mci,
+                                             const MV* __restrict__ mv, const int* __restrict__ pc,
+                                             const MV* __restrict__ pv, MV* tmp) {
     unsigned mask = 0;
-    for (int s = 0; s < 9; ++s) {
-        int i = qc[(size_t)I * 9 + s];
-        if (i < 0) break;
-        int p0 = mrp ? mrp[i] : 0, p1 = mrp ? mrp[i + 1] : 1;
-        for (int p = p0; p < p1; ++p) {
-            int j = mrp ? mci[p] : i;
+    int p0 = mrp ? mrp[i] : 0, p1 = mrp ? mrp[i + 1] : 1;
+    for (int p = p0; p < p1; ++p) {
+        int j = mrp ? mci[p] : i;
+        MV m = (VALS && mrp) ? mv[p] : (MV)1;
+        int Js[4];
+        MV ps[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                int J = pc[(size_t)j * 4 + t];
-                if (J >= 0) mask |= 1u << box_slot(Ia, Ib, J, dcy, ncx, ncy, periodic);
+        for (int t = 0; t < 4; ++t) {
+            Js[t] = pc[(size_t)j * 4 + t];
+            if (VALS) ps[t] = pv[(size_t)j * 4 + t];
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (Js[t] < 0) continue;
+            int sl = box_slot(Ia, Ib, Js[t], dcy, ncx, ncy, periodic);
+            mask |= 1u << sl;
+            if (VALS) {
+                MV c = m * ps[t];
+#pragma unroll
+                for (int u = 0; u < 9; ++u) tmp[u] += (u == sl) ? c : (MV)0;
             }
         }
     }
-    // columns of distinct slots are distinct (coarse sides >= 3)
-    cnt[I] = __popc(mask);
-    mask_out[I] = (unsigned short)mask;
+    return mask;
 }
 
-// Numeric pass: row I of Q (M P) accumulated as sum_i q_Ii (sum_j m_ij p_jJ)
-// in Q-row order, M-row order and P-row order (fixed order), written in
-// ascending coarse column at crp[I].
+// Symbolic pass of Q (M P): 9-bit mask of the coarse box slots reached by row
+// I (every coarse stencil lies in that box: Q, M and P each reach one grid
+// step).  cnt[I] = number of distinct columns.  M == identity when mrp is null.
+__global__ void __launch_bounds__(GAL_THREADS)
+k_galerkin_symbolic(int nc, FastDiv dcy, int ncx, int ncy, int periodic,
+                    const int* __restrict__ qc, const int* __restrict__ mrp,
+                    const int* __restrict__ mci, const int* __restrict__ pc,
+                    int* __restrict__ cnt, unsigned short* __restrict__ mask_out) {
+    __shared__ unsigned sm[GAL_THREADS];
+    const int lr = threadIdx.x / 9, s = threadIdx.x % 9;
+    const int I = xcd_tile(blockIdx.x, gridDim.x) * GAL_ROWS + lr;
+    unsigned mask = 0;
+    if (I < nc) {
+        int i = qc[(size_t)I * 9 + s];
+        if (i >= 0) {
+            int Ia = (int)dcy.div((uint32_t)I), Ib = I - Ia * ncy;
+            mask = gal_slot<float, false>(I, Ia, Ib, i, dcy, ncx, ncy, periodic, mrp, mci, (const float*)nullptr,
+                                          pc, (const float*)nullptr, nullptr);
+        }
+    }
+    sm[threadIdx.x] = mask;
+    __syncthreads();
+    if (s == 0 && I < nc) {
+        unsigned m = 0;
+        for (int u = 0; u < 9; ++u) m |= sm[threadIdx.x + u];
+        // columns of distinct slots are distinct (coarse sides >= 3)
+        cnt[I] = __popc(m);
+        mask_out[I] = (unsigned short)m;
+    }
+}
+
+// Numeric pass: row I of Q (M P) = sum_s q_Is (sum_j m_ij p_jJ) with the Q
+// slots added in order s = 0..8 (fixed order), written in ascending coarse
+// column at crp[I].
 template <typename MV>
-__global__ void __launch_bounds__(BAMG_BLK)
+__global__ void __launch_bounds__(GAL_THREADS)
 k_galerkin_numeric(int nc, FastDiv dcy, int ncx, int ncy, int periodic,
                    const int* __restrict__ qc, const MV* __restrict__ qv,
                    const int* __restrict__ mrp, const int* __restrict__ mci, const MV* __restrict__ mv,
                    const int* __restrict__ pc, const MV* __restrict__ pv,
                    const unsigned short* __restrict__ mask_in, const int* __restrict__ crp,
                    int* __restrict__ cci, MV* __restrict__ cv) {
-    int I = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
-    if (I >= nc) return;
-    int Ia = (int)dcy.div((uint32_t)I), Ib = I - Ia * ncy;
-    MV acc[9];
+    __shared__ MV sv[GAL_THREADS][9];
+    const int lr = threadIdx.x / 9, s = threadIdx.x % 9;
+    const int I = xcd_tile(blockIdx.x, gridDim.x) * GAL_ROWS + lr;
+    MV tmp[9];
 #pragma unroll
-    for (int s = 0; s < 9; ++s) acc[s] = 0;
-    for (int s = 0; s < 9; ++s) {
+    for (int u = 0; u < 9; ++u) tmp[u] = 0;
+    int Ia = 0, Ib = 0;
+    if (I < nc) {
+        Ia = (int)dcy.div((uint32_t)I); Ib = I - Ia * ncy;
         int i = qc[(size_t)I * 9 + s];
-        if (i < 0) break;
-        MV q = qv[(size_t)I * 9 + s];
-        MV tmp[9];
+        if (i >= 0) {
+            MV q = qv[(size_t)I * 9 + s];
+            gal_slot<MV, true>(I, Ia, Ib, i, dcy, ncx, ncy, periodic, mrp, mci, mv, pc, pv, tmp);
 #pragma unroll
-        for (int u = 0; u < 9; ++u) tmp[u] = 0;
-        int p0 = mrp ? mrp[i] : 0, p1 = mrp ? mrp[i + 1] : 1;
-        for (int p = p0; p < p1; ++p) {
-            int j = mrp ? mci[p] : i;
-            MV m = mrp ? mv[p] : (MV)1;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                int J = pc[(size_t)j * 4 + t];
-                if (J < 0) continue;
-                int sl = box_slot(Ia, Ib, J, dcy, ncx, ncy, periodic);
-                MV c = m * pv[(size_t)j * 4 + t];
-#pragma unroll
-                for (int u = 0; u < 9; ++u) tmp[u] += (u == sl) ? c : (MV)0;
-            }
+            for (int u = 0; u < 9; ++u) tmp[u] = q * tmp[u];
         }
-#pragma unroll
-        for (int u = 0; u < 9; ++u) acc[u] += q * tmp[u];
     }
+#pragma unroll
+    for (int u = 0; u < 9; ++u) sv[threadIdx.x][u] = tmp[u];
+    __syncthreads();
+    if (I >= nc) return;
+    // thread (I, s) finalises box slot u = s of row I
+    const int u = s;
     unsigned mask = mask_in[I];
-    int base = crp[I];
-    // column of each slot, then rank among the active slots
+    if (!((mask >> u) & 1)) return;
+    MV acc = 0;
+    for (int t = 0; t < 9; ++t) acc += sv[lr * 9 + t][u];
     int col[9];
 #pragma unroll
-    for (int u = 0; u < 9; ++u) {
-        int a = Ia + u / 3 - 1, b = Ib + u % 3 - 1;
+    for (int w = 0; w < 9; ++w) {
+        int a = Ia + w / 3 - 1, b = Ib + w % 3 - 1;
         if (periodic) {
             a = a < 0 ? a + ncx : (a >= ncx ? a - ncx : a);
             b = b < 0 ? b + ncy : (b >= ncy ? b - ncy : b);
         }
-        col[u] = a * ncy + b;
+        col[w] = a * ncy + b;
     }
+    int rank = 0;
 #pragma unroll
-    for (int u = 0; u < 9; ++u) {
-        if (!((mask >> u) & 1)) continue;
-        int rank = 0;
-#pragma unroll
-        for (int t = 0; t < 9; ++t) rank += ((mask >> t) & 1) && (col[t] < col[u]);
-        cci[base + rank] = col[u];
-        cv[base + rank] = acc[u];
-    }
+    for (int t = 0; t < 9; ++t) rank += ((mask >> t) & 1) && (col[t] < col[u]);
+    cci[crp[I] + rank] = col[u];
+    cv[crp[I] + rank] = acc;
 }
 
 // ---------------------------------------------------------------- up-leg
