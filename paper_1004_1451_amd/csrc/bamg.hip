@@ -429,6 +429,81 @@ struct Engine : bamg_ctx {
         galerkin(l, profile);
     }
 
+    // Inverse of the padded coarsest operator [[B_11, 0], [0, 1]] into W by
+    // block LU of its block-tridiagonal (+ periodic corner) structure; the
+    // dense B_L is in W on entry.  Grid rows give blocks of b = ny <= 64.
+    double* btbuf = nullptr;
+    void block_tridiagonal_inverse(const GridH& g) {
+        const int nx = g.nx, b = g.ny, K = nx - 1, bb = b * b;
+        const bool arrow = g.periodic && nx >= 3;
+        if (!btbuf) btbuf = A.alloc<double>((size_t)5 * nx * bb);
+        double* Dk = btbuf;
+        double* Up = Dk + (size_t)nx * bb;
+        double* Lo = Up + (size_t)nx * bb;
+        double* Cl = Lo + (size_t)nx * bb;
+        double* Rw = Cl + (size_t)nx * bb;
+        {
+            dim3 grid(ceil_div(bb, BAMG_BLK), nx, arrow ? 5 : 3);
+            hipLaunchKernelGGL(k_bt_extract, grid, dim3(BAMG_BLK), 0, s, nx, b, (const double*)W, Dk, Up, Lo, Cl, Rw);
+            HIPCHK(hipGetLastError());
+        }
+        auto blk = [&](double* base, int k) { return base + (size_t)k * bb; };
+        auto inv = [&](int k) {
+            LAUNCH(k_gj_diag, 1, BAMG_BLK, s, b, 0, b, blk(Dk, k), (const double*)(sc + 10), sc + 11);
+        };
+        for (int k = 0; k < K; ++k) {
+            inv(k);
+            BlkOps g1{}, g2{};
+            if (k + 1 < K) {
+                int q = 0;
+                g1.A[q] = blk(Lo, k + 1); g1.B[q] = blk(Dk, k); g1.C[q] = blk(Lo, k + 1); g1.mode[q++] = 0;
+                if (arrow) { g1.A[q] = blk(Rw, k); g1.B[q] = blk(Dk, k); g1.C[q] = blk(Rw, k); g1.mode[q++] = 0; }
+                LAUNCH(k_blk_gemm, q, BAMG_BLK, s, b, g1);
+                q = 0;
+                g2.A[q] = blk(Lo, k + 1); g2.B[q] = blk(Up, k); g2.C[q] = blk(Dk, k + 1); g2.mode[q++] = 1;
+                if (arrow) {
+                    double* colK = (k + 1 < K - 1) ? blk(Cl, k + 1) : blk(Up, k + 1);
+                    double* rowK = (k + 1 < K - 1) ? blk(Rw, k + 1) : blk(Lo, K);
+                    g2.A[q] = blk(Lo, k + 1); g2.B[q] = blk(Cl, k); g2.C[q] = colK; g2.mode[q++] = 1;
+                    g2.A[q] = blk(Rw, k); g2.B[q] = blk(Up, k); g2.C[q] = rowK; g2.mode[q++] = 1;
+                    g2.A[q] = blk(Rw, k); g2.B[q] = blk(Cl, k); g2.C[q] = blk(Dk, K); g2.mode[q++] = 1;
+                }
+                LAUNCH(k_blk_gemm, q, BAMG_BLK, s, b, g2);
+            } else {
+                g1.A[0] = blk(Lo, K); g1.B[0] = blk(Dk, k); g1.C[0] = blk(Lo, K); g1.mode[0] = 0;
+                LAUNCH(k_blk_gemm, 1, BAMG_BLK, s, b, g1);
+                g2.A[0] = blk(Lo, K); g2.B[0] = blk(Up, k); g2.C[0] = blk(Dk, K); g2.mode[0] = 1;
+                LAUNCH(k_blk_gemm, 1, BAMG_BLK, s, b, g2);
+            }
+        }
+        inv(K);
+        // forward substitution on the identity: W[k] = E_k - sum L_kj W[j]
+        const long long nn = (long long)nL * nL;
+        LAUNCH(k_identity, nblk(nn), BAMG_BLK, s, nn, nL, W);
+        const int ct = ceil_div(nL, 64);
+        for (int k = 1; k < K; ++k)
+            LAUNCH(k_bt_strip, ct, BAMG_BLK, s, b, nL, W, k, (const double*)blk(Lo, k), k - 1, (const double*)nullptr,
+                   0, (const double*)nullptr);
+        if (K >= 1) {
+            if (arrow)
+                for (int j = 0; j < K - 1; j += 2) {
+                    const double* A2 = j + 1 < K - 1 ? blk(Rw, j + 1) : nullptr;
+                    LAUNCH(k_bt_strip, ct, BAMG_BLK, s, b, nL, W, K, (const double*)blk(Rw, j), j, A2, j + 1,
+                           (const double*)nullptr);
+                }
+            LAUNCH(k_bt_strip, ct, BAMG_BLK, s, b, nL, W, K, (const double*)blk(Lo, K), K - 1, (const double*)nullptr,
+                   0, (const double*)nullptr);
+        }
+        // back substitution: W[k] = Dinv_k (W[k] - U_k W[k+1] - C_k W[K])
+        LAUNCH(k_bt_strip, ct, BAMG_BLK, s, b, nL, W, K, (const double*)nullptr, 0, (const double*)nullptr, 0,
+               (const double*)blk(Dk, K));
+        for (int k = K - 1; k >= 0; --k) {
+            const double* A2 = (arrow && k < K - 1) ? blk(Cl, k) : nullptr;
+            LAUNCH(k_bt_strip, ct, BAMG_BLK, s, b, nL, W, k, (const double*)blk(Up, k), k + 1, A2, K,
+                   (const double*)blk(Dk, k));
+        }
+    }
+
     // Dense pseudo-inverse of the coarsest operator into W, null vector y.
     void coarsest_inverse() {
         auto& cl = L.back();
@@ -442,14 +517,18 @@ struct Engine : bamg_ctx {
         double big = 1e300;
         HIPCHK(hipMemcpyAsync(sc + 11, &big, sizeof(double), hipMemcpyHostToDevice, s));
         if (m > 0) {
-            const int tiles = ceil_div(m, 64);
-            const int ut = ceil_div(m, GJ_T);
-            for (int k0 = 0; k0 < m; k0 += GJ_NB) {
-                int nb = std::min(GJ_NB, m - k0);
-                LAUNCH(k_gj_diag, 1, BAMG_BLK, s, nL, k0, nb, W, (const double*)(sc + 10), sc + 11);
-                LAUNCH(k_gj_rowpanel, tiles, BAMG_BLK, s, m, nL, k0, nb, W);
-                LAUNCH(k_gj_update, ut * ut, BAMG_BLK, s, m, nL, k0, nb, W);
-                LAUNCH(k_gj_colpanel, tiles, BAMG_BLK, s, m, nL, k0, nb, W);
+            if (cl.g.ny <= GJ_NB) {
+                block_tridiagonal_inverse(cl.g);
+            } else {
+                const int tiles = ceil_div(m, 64);
+                const int ut = ceil_div(m, GJ_T);
+                for (int k0 = 0; k0 < m; k0 += GJ_NB) {
+                    int nb = std::min(GJ_NB, m - k0);
+                    LAUNCH(k_gj_diag, 1, BAMG_BLK, s, nL, k0, nb, W, (const double*)(sc + 10), sc + 11);
+                    LAUNCH(k_gj_rowpanel, tiles, BAMG_BLK, s, m, nL, k0, nb, W);
+                    LAUNCH(k_gj_update, ut * ut, BAMG_BLK, s, m, nL, k0, nb, W);
+                    LAUNCH(k_gj_colpanel, tiles, BAMG_BLK, s, m, nL, k0, nb, W);
+                }
             }
         }
         LAUNCH(k_zero_border, nblk(nL), BAMG_BLK, s, nL, W);

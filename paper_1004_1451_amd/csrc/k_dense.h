@@ -61,7 +61,8 @@ __global__ void k_absmax_partial(long long n, const double* __restrict__ a, doub
 __global__ void __launch_bounds__(BAMG_BLK)
 k_gj_diag(int ld, int k0, int nb, double* __restrict__ A, const double* __restrict__ scale,
           double* __restrict__ minpiv) {
-    __shared__ double prow[2][GJ_NB], pcol[2][GJ_NB];
+    // two copies of the block: step k reads copy k&1 and writes copy (k+1)&1
+    __shared__ double M[2][GJ_NB][GJ_NB + 1];
     const int tid = threadIdx.x;
     const int r0 = (tid / 16) * 4, c0 = (tid % 16) * 4;
     double S[4][4];
@@ -71,44 +72,34 @@ k_gj_diag(int ld, int k0, int nb, double* __restrict__ A, const double* __restri
         for (int b = 0; b < 4; ++b) {
             int r = r0 + a, c = c0 + b;
             S[a][b] = (r < nb && c < nb) ? A[(size_t)(k0 + r) * ld + k0 + c] : (r == c ? 1.0 : 0.0);
+            M[0][r][c] = S[a][b];
         }
     const double sc = *scale;
     double mp = 1e300;
+    __syncthreads();
     for (int k = 0; k < GJ_NB; ++k) {
-        const int buf = k & 1;
-        // publish pivot row k and pivot column k (before this step's update)
-        if (k >= r0 && k < r0 + 4) {
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-                if (r0 + a == k)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) prow[buf][c0 + b] = S[a][b];
-        }
-        if (k >= c0 && k < c0 + 4) {
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                if (c0 + b == k)
-#pragma unroll
-                    for (int a = 0; a < 4; ++a) pcol[buf][r0 + a] = S[a][b];
-        }
-        __syncthreads();
-        const double piv = prow[buf][k];
-        if (tid == 0 && k < nb) mp = fmin(mp, fabs(piv) / sc);
+        const int rd = k & 1, wr = rd ^ 1;
+        const double piv = M[rd][k][k];
         const double ip = 1.0 / piv;
+        if (tid == 0 && k < nb) mp = fmin(mp, fabs(piv) / sc);
+        double f[4], pr[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int r = r0 + a;
-            const double f = pcol[buf][r];
+        for (int a = 0; a < 4; ++a) f[a] = M[rd][r0 + a][k];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) pr[b] = M[rd][k][c0 + b] * ip;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const int c = c0 + b;
-                const double pr = prow[buf][c];
-                double v;
-                if (r == k) v = (c == k) ? ip : pr * ip;
-                else v = (c == k) ? -f * ip : S[a][b] - f * (pr * ip);
+                const bool rk = (r0 + a) == k, ck = (c0 + b) == k;
+                double v = S[a][b] - f[a] * pr[b];
+                v = ck ? -f[a] * ip : v;
+                v = rk ? pr[b] : v;
+                v = (rk && ck) ? ip : v;
                 S[a][b] = v;
+                M[wr][r0 + a][c0 + b] = v;
             }
-        }
+        __syncthreads();
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -293,6 +284,183 @@ __global__ void k_project_w(int n, double* __restrict__ W, const double* __restr
     int i = (int)(e / n), j = (int)(e % n);
     double inv_n = 1.0 / n;
     W[e] = W[e] - s[i] * inv_n - y[i] * (u[j] - sc[0] * inv_n) / sc[1];
+}
+
+// ---------------------------------------------------------------- block-tridiagonal inverse
+// On the coarse grid (state s = a*ny + b, stencil within the 3x3 box) B_L is
+// block tridiagonal in the grid rows a, with blocks of size b = ny, plus the
+// two corner blocks (0, K) and (K, 0) when periodic (K = nx - 1).  The padded
+// matrix Bh = B_L with its last row and column replaced by e_n (so that
+// Bh^-1 = [[B_11^-1, 0], [0, 1]]) is factored by block LU without pivoting,
+// eliminating block rows 0..K-1 in order; with the corners the fill stays in
+// block column K and block row K ("arrow").  Compact factor storage, each an
+// array of nx blocks of b x b (row-major):
+//   Dk[k]  diagonal block, replaced by its inverse;
+//   Up[k]  block (k, k+1);   Lo[k]  block (k, k-1) -> multiplier;
+//   Cl[k]  block (k, K) for k < K-1;   Rw[k]  block (K, k) for k < K-1 ->
+//   multiplier.
+// Then Bh^-1 is formed in the dense buffer by block forward substitution on
+// the identity and block back substitution.
+
+// Extract the blocks of Bh from the dense B_L (ld n = nx*b).
+__global__ void k_bt_extract(int nx, int b, const double* __restrict__ A, double* __restrict__ Dk,
+                             double* __restrict__ Up, double* __restrict__ Lo, double* __restrict__ Cl,
+                             double* __restrict__ Rw) {
+    const int n = nx * b, K = nx - 1, bb = b * b;
+    const int k = blockIdx.y, kind = blockIdx.z;
+    for (int e = blockIdx.x * BAMG_BLK + threadIdx.x; e < bb; e += gridDim.x * BAMG_BLK) {
+        int r = e / b, c = e % b;
+        int bi, bj;
+        double* dst;
+        switch (kind) {
+            case 0: bi = k; bj = k; dst = Dk; break;
+            case 1: if (k >= K) return; bi = k; bj = k + 1; dst = Up; break;
+            case 2: if (k < 1) return; bi = k; bj = k - 1; dst = Lo; break;
+            case 3: if (k >= K - 1) return; bi = k; bj = K; dst = Cl; break;
+            default: if (k >= K - 1) return; bi = K; bj = k; dst = Rw; break;
+        }
+        int gi = bi * b + r, gj = bj * b + c;
+        double v = A[(size_t)gi * n + gj];
+        if (gi == n - 1 || gj == n - 1) v = (gi == gj) ? 1.0 : 0.0;
+        dst[(size_t)k * bb + e] = v;
+    }
+}
+
+// Small dense products on b x b blocks (b <= 64), one workgroup per product:
+// C = A B (mode 0, C may alias A) or C -= A B (mode 1).
+struct BlkOps {
+    const double* A[4];
+    const double* B[4];
+    double* C[4];
+    int mode[4];
+};
+__global__ void __launch_bounds__(BAMG_BLK)
+k_blk_gemm(int b, BlkOps ops) {
+    __shared__ double AsT[GJ_NB][GJ_NB + 2];
+    __shared__ double Bs[GJ_NB][GJ_NB + 2];
+    const int q = blockIdx.x;
+    const double* A = ops.A[q];
+    const double* Bm = ops.B[q];
+    double* C = ops.C[q];
+    const int mode = ops.mode[q];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < GJ_NB * GJ_NB; e += BAMG_BLK) {
+        int r = e / GJ_NB, c = e % GJ_NB;
+        bool ok = r < b && c < b;
+        AsT[c][r] = ok ? A[r * b + c] : 0.0;
+        Bs[r][c] = ok ? Bm[r * b + c] : 0.0;
+    }
+    __syncthreads();
+    const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+    for (int t = 0; t < b; ++t) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) av[a] = AsT[t][tr + a];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bv[c] = Bs[t][tc + c];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[a][c] += av[a] * bv[c];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            int r = tr + a, cc = tc + c;
+            if (r < b && cc < b) {
+                if (mode == 0) C[r * b + cc] = acc[a][c];
+                else C[r * b + cc] -= acc[a][c];
+            }
+        }
+}
+
+// Block row kout of the n x n buffer W (rows kout*b ..), columns of this
+// workgroup's 64-column tile:  T = W[kout] - A1 W[j1] - A2 W[j2] (A1/A2 null
+// = absent), then W[kout] = Dinv T (Dinv null = T).  b <= 64.
+__global__ void __launch_bounds__(BAMG_BLK)
+k_bt_strip(int b, int n, double* __restrict__ W, int kout, const double* __restrict__ A1, int j1,
+           const double* __restrict__ A2, int j2, const double* __restrict__ Dinv) {
+    __shared__ double Ms[GJ_NB][GJ_NB + 1];
+    __shared__ double Xs[GJ_NB][64 + 1];
+    const int tid = threadIdx.x;
+    const int c0 = blockIdx.x * 64;
+    const int w = min(64, n - c0);
+    const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+    double T[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int r = tr + a, c = tc + q;
+            T[a][q] = (r < b && c < w) ? W[(size_t)(kout * b + r) * n + c0 + c] : 0.0;
+        }
+    for (int term = 0; term < 2; ++term) {
+        const double* M = term == 0 ? A1 : A2;
+        const int jb = term == 0 ? j1 : j2;
+        if (!M) continue;
+        __syncthreads();
+        for (int e = tid; e < b * b; e += BAMG_BLK) Ms[e / b][e % b] = M[e];
+        for (int e = tid; e < b * 64; e += BAMG_BLK) {
+            int r = e / 64, c = e % 64;
+            Xs[r][c] = c < w ? W[(size_t)(jb * b + r) * n + c0 + c] : 0.0;
+        }
+        __syncthreads();
+        for (int t = 0; t < b; ++t) {
+            double mv[4], xv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) mv[a] = (tr + a < b) ? Ms[tr + a][t] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xv[q] = Xs[t][tc + q];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) T[a][q] -= mv[a] * xv[q];
+        }
+    }
+    if (Dinv) {
+        __syncthreads();
+        for (int e = tid; e < b * b; e += BAMG_BLK) Ms[e / b][e % b] = Dinv[e];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (tr + a < GJ_NB) Xs[tr + a][tc + q] = T[a][q];
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) T[a][q] = 0.0;
+        for (int t = 0; t < b; ++t) {
+            double mv[4], xv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) mv[a] = (tr + a < b) ? Ms[tr + a][t] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xv[q] = Xs[t][tc + q];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) T[a][q] += mv[a] * xv[q];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int r = tr + a, c = tc + q;
+            if (r < b && c < w) W[(size_t)(kout * b + r) * n + c0 + c] = T[a][q];
+        }
+}
+
+// W = I (n x n).
+__global__ void k_identity(long long nn, int n, double* __restrict__ W) {
+    long long e = (long long)blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (e < nn) W[e] = (e / n == e % n) ? 1.0 : 0.0;
 }
 
 // ---------------------------------------------------------------- small vectors
