@@ -31,6 +31,9 @@
  *   - Return value 0 on success or a negative BAMG_E* code; no exception or
  *     abort crosses the ABI.  bamg_last_error() gives a message for the last
  *     failure of the calling thread.
+ *   - Environment: BAMG_POISON=1 fills every floating-point allocation of a
+ *     handle with NaN bits (integer ones with zero) when it is made; for
+ *     tests that no kernel reads memory it has not written.  Costs one fill.
  */
 #ifndef BAMG_H
 #define BAMG_H
@@ -171,6 +174,36 @@ int bamg_setup(int64_t n, const int32_t* row_ptr, const int32_t* col_idx,
 int bamg_solve(bamg_handle h, double* x, double tol, int32_t max_cycles,
                uint32_t flags, bamg_solve_info* info);
 
+/* Batched setup: nchains independent chains in one handle, solved together.
+   The same construction as bamg_setup, applied to every chain (Algorithm 3
+   per chain); chains never interact.  The caller concatenates the chains
+   block-diagonally: chain c owns rows and columns [chain_row_off[c],
+   chain_row_off[c+1]) of the CSR (host int64 array of nchains+1 offsets,
+   chain_row_off[0] = 0, n = chain_row_off[nchains]); a column outside the
+   row's own chain is EINVAL.  grids: host array of nchains grids, one per
+   chain (local state numbering).  Chains may differ in size and depth; with
+   levels = 0 each chain coarsens until its own size <= coarse_max.  Every
+   chain's coarsest grid must have ny <= 64 when nchains > 1 (EUNSUPPORTED
+   otherwise).  bamg_export is limited to nchains = 1; the other entry points
+   work on all chains at once.  1 <= nchains <= 4096.  Same errors as
+   bamg_setup. */
+int bamg_setup_batched(int32_t nchains, const int64_t* chain_row_off,
+                       const int32_t* row_ptr, const int32_t* col_idx,
+                       const double* val, const bamg_grid* grids, int32_t r,
+                       const bamg_options* opt, void* stream, bamg_handle* out);
+
+/* Solve every chain of a batched handle (or of a bamg_setup handle, as one
+   chain) with lockstep flexible GMRES: each chain keeps its own Krylov
+   scalars and stops on its own tolerance.  x: device, n doubles in the
+   caller's concatenated order; each chain's block ends >= 0 and sums to 1.
+   chain_status (host int32[nchains], may be NULL): 1 converged, 0 not.
+   chain_residual (host double[nchains], may be NULL): ||B_c x_c||_1/||x_c||_1.
+   info: cycles, restarts and history hold the worst chain.  Returns 0 when
+   every chain converged, otherwise ENOCONV; EINVAL, EDEVICE. */
+int bamg_solve_batched(bamg_handle h, double* x, double tol, int32_t max_cycles,
+                       uint32_t flags, int32_t* chain_status,
+                       double* chain_residual, bamg_solve_info* info);
+
 /* Release everything the handle owns.  NULL is allowed. */
 int bamg_free(bamg_handle h);
 
@@ -189,7 +222,8 @@ int bamg_level_info_get(bamg_handle h, int32_t l, bamg_level_info* out);
 int bamg_export(bamg_handle h, int32_t l, int32_t what, void* dst, size_t bytes);
 
 /* One application of the V-cycle preconditioner on level 0: e = C f
-   (device vectors of n doubles).  Synchronises the stream. */
+   (device vectors of n doubles; for a batched handle all chains at once, in
+   the caller's concatenated order).  Synchronises the stream. */
 int bamg_apply_vcycle(bamg_handle h, const double* f, double* e);
 
 /* nu omega-Jacobi sweeps X <- X + omega D^-1 (F - B X) on caller data

@@ -29,7 +29,8 @@ ERROR_NAMES = {EINVAL: "EINVAL", ENOTSTOCH: "ENOTSTOCH", EZERODIAG: "EZERODIAG",
 
 # every symbol include/bamg.h declares
 EXPORTS = ["bamg_options_default", "bamg_setup", "bamg_solve", "bamg_free", "bamg_last_error", "bamg_get_stats",
-           "bamg_level_info_get", "bamg_export", "bamg_apply_vcycle", "bamg_relax"]
+           "bamg_level_info_get", "bamg_export", "bamg_apply_vcycle", "bamg_relax", "bamg_setup_batched",
+           "bamg_solve_batched"]
 
 
 class BamgError(RuntimeError):
@@ -103,6 +104,10 @@ def load():
     lib.bamg_apply_vcycle.restype = C.c_int
     lib.bamg_relax.argtypes = [i64, vp, vp, vp, vp, vp, i32, dbl, i32, vp]
     lib.bamg_relax.restype = C.c_int
+    lib.bamg_setup_batched.argtypes = [i32, vp, vp, vp, vp, vp, i32, C.POINTER(Options), vp, C.POINTER(vp)]
+    lib.bamg_setup_batched.restype = C.c_int
+    lib.bamg_solve_batched.argtypes = [vp, vp, dbl, i32, C.c_uint32, vp, vp, C.POINTER(SolveInfo)]
+    lib.bamg_solve_batched.restype = C.c_int
     _lib = lib
     return lib
 
@@ -200,6 +205,52 @@ class Hierarchy:
             self.close()
         except Exception:
             pass
+
+
+def concat_chains(chains):
+    """Block-diagonal concatenation: (row offsets, row_ptr, col_idx, val, grids) as numpy arrays."""
+    off = np.zeros(len(chains) + 1, dtype=np.int64)
+    for c, ch in enumerate(chains):
+        off[c + 1] = off[c] + ch.n
+    nnz = np.cumsum([0] + [len(ch.col_idx) for ch in chains])
+    rp = np.concatenate([np.asarray(ch.row_ptr[:-1], dtype=np.int64) + nnz[c] for c, ch in enumerate(chains)]
+                        + [np.array([nnz[-1]], dtype=np.int64)]).astype(np.int32)
+    ci = np.concatenate([np.asarray(ch.col_idx, dtype=np.int64) + off[c] for c, ch in enumerate(chains)]).astype(np.int32)
+    v = np.concatenate([np.asarray(ch.val, dtype=np.float64) for ch in chains])
+    grids = np.array([(ch.nx, ch.ny, int(bool(ch.periodic))) for ch in chains], dtype=np.int32)
+    return off, rp, ci, v, grids
+
+
+class BatchedHierarchy(Hierarchy):
+    """Owns a bamg_handle made by bamg_setup_batched (several chains, one handle)."""
+
+    def __init__(self, chains, r, options: Options | None = None, stream=None):
+        import torch
+        lib = load()
+        self._h = C.c_void_p()
+        off, rp, ci, v, grids = concat_chains(chains)
+        self.nchains = len(chains)
+        self.offsets = off
+        self.n = int(off[-1])
+        drp = torch.as_tensor(rp, device="cuda")
+        dci = torch.as_tensor(ci, device="cuda")
+        dv = torch.as_tensor(v, device="cuda")
+        garr = (Grid * self.nchains)(*[Grid(int(a), int(b), int(c)) for a, b, c in grids])
+        opts = options if options is not None else default_options()
+        _check(lib.bamg_setup_batched(self.nchains, off.ctypes.data_as(C.c_void_p), C.c_void_p(drp.data_ptr()),
+                                      C.c_void_p(dci.data_ptr()), C.c_void_p(dv.data_ptr()), garr, int(r),
+                                      C.byref(opts), _stream_ptr(stream), C.byref(self._h)))
+
+    def solve_batched(self, x, tol=1e-10, max_cycles=200, use_guess=False):
+        """Returns (info, per-chain status int32 array, per-chain residual array)."""
+        info = SolveInfo()
+        status = np.zeros(self.nchains, dtype=np.int32)
+        resid = np.zeros(self.nchains, dtype=np.float64)
+        rc = load().bamg_solve_batched(self._h, C.c_void_p(x.data_ptr()), float(tol), int(max_cycles),
+                                       USE_GUESS if use_guess else 0, status.ctypes.data_as(C.c_void_p),
+                                       resid.ctypes.data_as(C.c_void_p), C.byref(info))
+        _check(rc, allow=(ENOCONV,))
+        return info, status, resid
 
 
 def relax(row_ptr, col_idx, val, X, R, omega=0.7, nu=1, F=None, stream=None):

@@ -1,9 +1,14 @@
 // Host orchestration and C ABI of the Bootstrap AMG library (see bamg.h).
 //
-// One handle = one hierarchy on one HIP stream.  Every numerical step runs in
-// the kernels of k_sparse.h / k_dense.h / k_solve.h; the host plans levels,
-// allocates, launches, and reads back a few scalars (error flags, the number
-// of coarsest eigenvector columns, convergence estimates).
+// One handle = one hierarchy of one or more chains on one HIP stream.  Several
+// chains form one block-diagonal system: on every level the rows of each
+// chain are contiguous, the chains ordered by depth (deepest first) so that
+// the chains that continue to the next level are always a row prefix.  Every
+// phase of the setup and of the cycle is one launch over all chains; the
+// per-chain small work (coarsest level, Arnoldi, GMRES scalars) is batched
+// over the chains inside its kernels.  The host plans levels, allocates,
+// launches, and reads back a few scalars (error flags, the number of coarsest
+// eigenvector columns, convergence estimates).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -11,14 +16,18 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <numeric>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/bamg.h"
 #include "common.h"
+#include "k_coarse.h"
 #include "k_dense.h"
 #include "k_solve.h"
 #include "k_sparse.h"
@@ -47,15 +56,20 @@ struct BamgError : std::runtime_error {
         if (e_ != hipSuccess) fail(BAMG_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
     } while (0)
 
-#define LAUNCH(kern, grid, block, s, ...)                           \
-    do {                                                            \
+#define LAUNCH(kern, grid, block, s, ...)                                    \
+    do {                                                                     \
         hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, __VA_ARGS__); \
-        HIPCHK(hipGetLastError());                                  \
+        HIPCHK(hipGetLastError());                                           \
     } while (0)
 
 inline int nblk(long long n) { return (int)std::max<long long>(1, (n + BAMG_BLK - 1) / BAMG_BLK); }
-constexpr int RED_PARTS = 1024;       // fixed partition of every FP64 reduction
-constexpr int MDOT_BLOCKS = 1024;     // fixed row partition of the GMRES multi-dots
+constexpr int SEG_PARTS = 64;     // fixed chunks per chain of the per-chain reductions
+constexpr int MDOT_PARTS = 64;    // fixed chunks per chain of the GMRES multi-dots
+constexpr int WS = 64;            // stride of the per-chain TV weights
+constexpr int KV = 16;            // stride of the per-chain eigen tables
+constexpr int SCS = 16;           // stride of the per-chain scalars
+constexpr int NS = 4, LSS = 32;   // strides of the Hessenberg selection outputs
+constexpr int GT_RCH = 128;       // row chunk of the y^T W partials
 
 struct GridH {
     int nx, ny, periodic;
@@ -65,7 +79,6 @@ struct GridH {
         if (periodic) return nx % 2 == 0 && ny % 2 == 0 && nx / 2 >= 3 && ny / 2 >= 3;
         return n() > 1;
     }
-    GridDev dev() const { return GridDev{nx, ny, periodic, FastDiv((uint32_t)ny)}; }
 };
 
 // Levels 0..L: "levels" counts the finest; 0 = coarsen while n > coarse_max.
@@ -85,9 +98,19 @@ std::vector<GridH> level_plan(GridH g, int levels, int coarse_max) {
 }
 
 // ------------------------------------------------------------------ memory
+// BAMG_POISON=1 in the environment: floating-point allocations start as NaN
+// (all bits set) and integer ones as zero, so that a read of memory no kernel
+// has written shows up in the results instead of depending on what the
+// allocator hands out.
+bool poison_enabled() {
+    const char* e = getenv("BAMG_POISON");
+    return e && e[0] == '1';
+}
+
 struct Arena {
     hipStream_t s = nullptr;
     size_t bytes = 0, budget = 0;
+    bool poison = poison_enabled();
     std::vector<void*> ptrs;
     template <typename X>
     X* alloc(size_t count) {
@@ -101,7 +124,14 @@ struct Arena {
         }
         bytes += b;
         ptrs.push_back(p);
+        if (poison) HIPCHK(hipMemsetAsync(p, std::is_floating_point<X>::value ? 0xFF : 0x00, b, s));
         return (X*)p;
+    }
+    template <typename X>
+    X* upload(const std::vector<X>& v) {
+        X* p = alloc<X>(v.size());
+        if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), sizeof(X) * v.size(), hipMemcpyHostToDevice, s));
+        return p;
     }
     void release() {
         for (void* p : ptrs) (void)hipFreeAsync(p, s);
@@ -112,27 +142,38 @@ struct Arena {
 
 template <typename T>
 struct Csr {
-    int n = 0, cap = 0;
+    int cap = 0;
     int* rp = nullptr;
     int* ci = nullptr;
     T* v = nullptr;
 };
 
+// Rows of one level: all present chains, continuing chains first.
 template <typename T>
 struct Level {
-    GridH g{};
-    int n = 0;
-    Csr<T> B, Tm;           // Tm.rp == nullptr: T = I (finest level)
+    int nch = 0, ncont = 0;          // present chains, chains with a next level
+    int rows = 0, cont_rows = 0;     // all rows, rows of continuing chains
+    std::vector<ChainGeo> geo;       // host copy
+    ChainGeo* dgeo = nullptr;        // device copy
+    Csr<T> B, Tm;                    // Tm.rp == nullptr: T = I (finest level)
     T* dinv = nullptr;
-    int* pc = nullptr;      // P: n x 4 (ELL)
+    int* pc = nullptr;               // P: cont_rows x 4 (ELL)
     T* pv = nullptr;
-    int* qc = nullptr;      // Q: n_{l+1} x 9 (ELL)
+    int* qc = nullptr;               // Q: next level rows x 9 (ELL)
     T* qv = nullptr;
-    T* U = nullptr;         // n x r relaxed test vectors
-    T* V = nullptr;         // n x nv eigenvector approximations
+    T* U = nullptr;                  // rows x r relaxed test vectors
+    T* V = nullptr;                  // rows x VS eigenvector approximations
     T *e = nullptr, *e2 = nullptr, *f = nullptr, *r = nullptr;   // cycle vectors
     unsigned short* mask = nullptr;
     int* cnt = nullptr;
+    bool zero_into_e2 = false;       // first smoothing sweep target (fixed buffers)
+};
+
+struct ChainH {
+    int uidx = 0;                    // caller's index
+    long long uoff = 0, n = 0;       // caller's row offset and size
+    GridH grid{};
+    std::vector<GridH> plan;
 };
 
 }  // namespace
@@ -141,7 +182,8 @@ struct Level {
 struct bamg_ctx {
     virtual ~bamg_ctx() {}
     virtual void setup(const int32_t* rp, const int32_t* ci, const double* val) = 0;
-    virtual int solve(double* x, double tol, int max_cycles, uint32_t flags, bamg_solve_info* info) = 0;
+    virtual int solve(double* x, double tol, int max_cycles, uint32_t flags, int32_t* status, double* resid,
+                      bamg_solve_info* info) = 0;
     virtual void level_info(int l, bamg_level_info* out) = 0;
     virtual void export_item(int l, int what, void* dst, size_t bytes) = 0;
     virtual void vcycle_apply(const double* f, double* e) = 0;
@@ -149,62 +191,69 @@ struct bamg_ctx {
     bamg_options o{};
     bamg_stats st{};
     int r = 0;
+    int nch = 1;
     long long n = 0;
-    GridH grid{};
+    std::vector<ChainH> chains;      // internal (depth-sorted) order
 };
 
 namespace {
 
 template <typename T>
 struct Engine : bamg_ctx {
+    static constexpr bool MIXED = sizeof(T) == 4;
     Arena A;
-    std::vector<GridH> plan;
     std::vector<Level<T>> L;
+    int VS = 7;                      // row stride of the eigenvector blocks
     // finest level in FP64 for the outer iteration
     int* b0rp = nullptr;
     int* b0ci = nullptr;
     double* b0v = nullptr;
     int nnz0 = 0;
-    // coarsest level
-    int nL = 0;
-    double* W = nullptr;     // B_L^+ (n_L x n_L)
-    float* Wf = nullptr;     // FP32 copy for the mixed cycle
-    double* y = nullptr;     // null vector
-    double* cvec = nullptr;  // T_L^T 1
-    double* bcol = nullptr;
-    double* tmpL = nullptr;  // n_L scratch vectors
-    double* tmpL2 = nullptr;
-    double* fL = nullptr;    // FP64 coarse right-hand side / solution
-    double* eL = nullptr;
-    // eigen tables (device): lam[2*8], kind[8], ent_col[8]
-    double* lam = nullptr;
-    int* kind = nullptr;
-    int* ent_col = nullptr;
-    int nv = 0, nent = 0;
-    double* x0 = nullptr;
-    // reductions
-    double* part = nullptr;
-    double* sc = nullptr;   // 64 device scalars
-    double* wts = nullptr;  // TV weights (<= 64)
-    int* err = nullptr;
-    int* itmp = nullptr;    // scan scratch
-    int* bsum = nullptr;
-    int* total = nullptr;
-    // FGMRES
-    double *Vk = nullptr, *Zk = nullptr, *wk = nullptr, *Hg = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr,
-           *ysol = nullptr, *hbuf = nullptr, *rvec = nullptr;
-    double *v64 = nullptr, *z64 = nullptr;   // V-cycle entry/exit in FP64
-    // Arnoldi
-    double *Vb = nullptr, *Hh = nullptr, *Hrow = nullptr, *sel_lam = nullptr, *sel_s = nullptr, *ritz_re = nullptr,
-           *ritz_im = nullptr;
+    bool reordered = false;
+    int *perm_src = nullptr, *perm_dst = nullptr, *perm_len = nullptr;   // caller -> internal
+    // coarsest levels (one per chain)
+    std::vector<CoarseDesc> cdh;
+    CoarseDesc* cd = nullptr;
+    int NVt = 0;                     // sum of coarsest sizes
+    int AMmax = 0, maxnL = 0, nxmax = 0;
+    double *Wp = nullptr, *Fp = nullptr, *ypool = nullptr, *cpool = nullptr, *bcolp = nullptr, *t1 = nullptr,
+           *t2 = nullptr, *rre = nullptr, *rim = nullptr, *gtpart = nullptr;
+    float* Wfp = nullptr;
+    double *scale = nullptr, *minpiv = nullptr, *cy = nullptr, *csc = nullptr, *dots = nullptr;
+    double *Vb = nullptr, *Hh = nullptr, *Hrow = nullptr, *sel_lam = nullptr, *sel_s = nullptr;
     int* nsel = nullptr;
-    double* ah = nullptr;   // Gram-Schmidt coefficients of one Arnoldi step
+    int HS = 1, HRS = 1, SS = 1, DS = 1;
+    bool dense_fallback = false;
+    // eigen tables
+    double* lam = nullptr;
+    int *kind = nullptr, *ent_col = nullptr, *nvc = nullptr, *nentc = nullptr;
+    std::vector<int> nvc_h;
+    int nvmax = 1;
+    double* x0 = nullptr;
+    // reductions / scalars
+    double* part = nullptr;
+    double* sc = nullptr;            // nch x SCS per-chain scalars
+    double* wts = nullptr;           // nch x WS TV weights
+    int* err = nullptr;
+    int *itmp = nullptr, *bsum = nullptr, *total = nullptr;
+    T* sweep_tmp = nullptr;
+    // FGMRES
+    int m_alloc = 0;
+    double *Vk = nullptr, *Zk = nullptr, *wk = nullptr, *Hg = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr,
+           *ysol = nullptr, *hbuf = nullptr, *rvec = nullptr, *est = nullptr, *xperm = nullptr;
+    int *act = nullptr, *kd = nullptr;
+    double *vin = nullptr, *vout = nullptr;   // permuted vectors of bamg_apply_vcycle
+    // graph of one cycle on fixed buffers
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap_s = nullptr;     // capture needs a stream other than the legacy default one
     // profiling
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_sweep, ev_gal, ev_ls;
 
-    static constexpr bool MIXED = sizeof(T) == 4;
-
     ~Engine() override {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap_s) (void)hipStreamDestroy(cap_s);
         for (auto* v : {&ev_sweep, &ev_gal, &ev_ls})
             for (auto& p : *v) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
         A.release();
@@ -220,20 +269,30 @@ struct Engine : bamg_ctx {
         sync();
         return v;
     }
+    template <typename X>
+    std::vector<X> getn(const X* p, size_t cnt) {
+        std::vector<X> v(cnt);
+        if (cnt) HIPCHK(hipMemcpyAsync(v.data(), p, sizeof(X) * cnt, hipMemcpyDeviceToHost, s));
+        sync();
+        return v;
+    }
     void zero(void* p, size_t bytes) { HIPCHK(hipMemsetAsync(p, 0, bytes, s)); }
 
-    void scan(int n, const int* cnt, int* out) {
-        int nb = nblk(n);
-        LAUNCH(k_scan_block, nb, BAMG_BLK, s, n, cnt, out, bsum);
+    void scan(int cnt_n, const int* cnt, int* out) {
+        int nb = nblk(cnt_n);
+        LAUNCH(k_scan_block, nb, BAMG_BLK, s, cnt_n, cnt, out, bsum);
         LAUNCH(k_scan_sums, 1, BAMG_BLK, s, nb, bsum, total);
-        LAUNCH(k_scan_add, nb, BAMG_BLK, s, n, out, bsum, total);
+        LAUNCH(k_scan_add, nb, BAMG_BLK, s, cnt_n, out, bsum, total);
     }
 
-    // reductions into device scalar *out
+    // per-chain reduction over the finest rows -> out[c * SCS]
     template <int OP>
-    void reduce(long long n, const double* a, const double* b, double* out) {
-        LAUNCH(k_reduce_partial<OP>, RED_PARTS, BAMG_BLK, s, n, a, b, part);
-        LAUNCH(k_reduce_final, 1, BAMG_BLK, s, RED_PARTS, part, out);
+    void seg_reduce(const double* a, const double* b, double* out) {
+        dim3 grid(SEG_PARTS, nch);
+        hipLaunchKernelGGL(k_seg_reduce_partial<OP>, grid, dim3(BAMG_BLK), 0, s, (const ChainGeo*)L[0].dgeo, a, b,
+                           part);
+        HIPCHK(hipGetLastError());
+        LAUNCH(k_seg_reduce_final, nch, BAMG_BLK, s, SEG_PARTS, (const double*)part, out, SCS);
     }
 
     std::pair<hipEvent_t, hipEvent_t> ev_begin() {
@@ -248,39 +307,76 @@ struct Engine : bamg_ctx {
         v.push_back(p);
     }
 
-    // -------------------------------------------------------------- setup
-    void allocate(int nnzA) {
-        const int nl = (int)plan.size();
-        const int kmax = std::max(1, o.n_eig) + 1;      // columns of V (a pair may add one)
-        L.resize(nl);
-        for (int l = 0; l < nl; ++l) {
+    // -------------------------------------------------------------- planning
+    void plan_levels() {
+        int depth = 0;
+        for (auto& c : chains) depth = std::max(depth, (int)c.plan.size());
+        L.resize(depth);
+        for (int l = 0; l < depth; ++l) {
             auto& lv = L[l];
-            lv.g = plan[l];
-            lv.n = (int)plan[l].n();
+            int off = 0;
+            for (int c = 0; c < nch; ++c) {
+                auto& ch = chains[c];
+                if ((int)ch.plan.size() <= l) break;     // depth-sorted: the rest are shorter
+                ChainGeo gg{};
+                const GridH& gh = ch.plan[l];
+                gg.off = off; gg.n = (int)gh.n();
+                gg.nx = gh.nx; gg.ny = gh.ny; gg.periodic = gh.periodic; gg.dy = FastDiv((uint32_t)gh.ny);
+                if ((int)ch.plan.size() > l + 1) {
+                    const GridH& gc = ch.plan[l + 1];
+                    gg.cn = (int)gc.n(); gg.ncx = gc.nx; gg.ncy = gc.ny; gg.dcy = FastDiv((uint32_t)gc.ny);
+                    ++lv.ncont;
+                } else {
+                    gg.cn = 0; gg.ncx = 1; gg.ncy = 1; gg.dcy = FastDiv(1u);
+                }
+                lv.geo.push_back(gg);
+                off += gg.n;
+            }
+            lv.nch = (int)lv.geo.size();
+            lv.rows = off;
+            lv.cont_rows = lv.ncont < lv.nch ? lv.geo[lv.ncont].off : off;
+        }
+        for (int l = 0; l + 1 < depth; ++l)
+            for (int c = 0; c < L[l].ncont; ++c) L[l].geo[c].coff = L[l + 1].geo[c].off;
+        // fixed buffers of the cycle: the first smoothing sweep writes where the
+        // parity of the remaining sweeps leaves the result in e
+        for (auto& lv : L) {
+            int flips = std::max(0, o.nu_pre - 1) + o.nu_post;
+            lv.zero_into_e2 = (flips % 2) == 1;
+        }
+    }
+
+    void allocate(int nnzA) {
+        const int depth = (int)L.size();
+        VS = std::max(1, o.n_eig) + 1;
+        for (int l = 0; l < depth; ++l) {
+            auto& lv = L[l];
+            const int n_l = lv.rows;
+            lv.dgeo = A.upload(lv.geo);
             if (l == 0) {
-                lv.B.cap = nnzA + lv.n;
+                lv.B.cap = nnzA + n_l;
             } else {
-                lv.B.cap = 9 * lv.n;
-                lv.Tm.cap = 9 * lv.n;
-                lv.Tm.rp = A.alloc<int>(lv.n + 1);
+                lv.B.cap = 9 * n_l;
+                lv.Tm.cap = 9 * n_l;
+                lv.Tm.rp = A.alloc<int>(n_l + 1);
                 lv.Tm.ci = A.alloc<int>(lv.Tm.cap);
                 lv.Tm.v = A.alloc<T>(lv.Tm.cap);
             }
-            lv.B.n = lv.n;
-            lv.B.rp = A.alloc<int>(lv.n + 1);
+            lv.B.rp = A.alloc<int>(n_l + 1);
             lv.B.ci = A.alloc<int>(lv.B.cap);
             lv.B.v = A.alloc<T>(lv.B.cap);
-            lv.dinv = A.alloc<T>(lv.n);
-            lv.U = A.alloc<T>((size_t)lv.n * r);
-            lv.V = A.alloc<T>((size_t)lv.n * kmax);
-            lv.e = A.alloc<T>(lv.n);
-            lv.e2 = A.alloc<T>(lv.n);
-            lv.f = A.alloc<T>(lv.n);
-            lv.r = A.alloc<T>(lv.n);
-            if (l + 1 < nl) {
-                int nc = (int)plan[l + 1].n();
-                lv.pc = A.alloc<int>((size_t)lv.n * 4);
-                lv.pv = A.alloc<T>((size_t)lv.n * 4);
+            lv.dinv = A.alloc<T>(n_l);
+            lv.U = A.alloc<T>((size_t)n_l * r);
+            lv.V = A.alloc<T>((size_t)n_l * VS);
+            zero(lv.V, sizeof(T) * (size_t)n_l * VS);
+            lv.e = A.alloc<T>(n_l);
+            lv.e2 = A.alloc<T>(n_l);
+            lv.f = A.alloc<T>(n_l);
+            lv.r = A.alloc<T>(n_l);
+            if (lv.ncont > 0) {
+                const int nc = L[l + 1].rows;
+                lv.pc = A.alloc<int>((size_t)lv.cont_rows * 4);
+                lv.pv = A.alloc<T>((size_t)lv.cont_rows * 4);
                 lv.qc = A.alloc<int>((size_t)nc * 9);
                 lv.qv = A.alloc<T>((size_t)nc * 9);
                 lv.mask = A.alloc<unsigned short>(nc);
@@ -296,408 +392,454 @@ struct Engine : bamg_ctx {
             b0ci = L[0].B.ci;
             b0v = (double*)L[0].B.v;
         }
-        nL = L.back().n;
-        W = A.alloc<double>((size_t)nL * nL);
-        if (MIXED) Wf = A.alloc<float>((size_t)nL * nL);
-        y = A.alloc<double>(nL);
-        cvec = A.alloc<double>(nL);
-        bcol = A.alloc<double>(nL);
-        tmpL = A.alloc<double>(nL);
-        tmpL2 = A.alloc<double>(nL);
-        fL = A.alloc<double>(nL);
-        eL = A.alloc<double>(nL);
-        lam = A.alloc<double>(2 * 16);
-        kind = A.alloc<int>(16);
-        ent_col = A.alloc<int>(16);
+        // coarsest descriptors: chain c's coarsest level is its last plan entry
+        long long woff = 0, boff = 0, aoff = 0;
+        int voff = 0;
+        AMmax = 0; maxnL = 0; nxmax = 0;
+        dense_fallback = false;
+        for (int c = 0; c < nch; ++c) {
+            const auto& ch = chains[c];
+            const int lc = (int)ch.plan.size() - 1;
+            const GridH& gh = ch.plan[lc];
+            CoarseDesc d{};
+            d.n = (int)gh.n(); d.nx = gh.nx; d.ny = gh.ny; d.periodic = gh.periodic; d.dy = FastDiv((uint32_t)gh.ny);
+            d.row0 = L[lc].geo[c].off;
+            d.voff = voff;
+            d.woff = woff;
+            d.boff = boff;
+            d.aoff = aoff;
+            d.am = (o.n_eig > 1) ? std::max(0, std::min({o.arnoldi_m, d.n - 1, HQR_MAXM})) : 0;
+            d.brp = L[lc].B.rp; d.bci = L[lc].B.ci; d.bv = L[lc].B.v;
+            d.trp = L[lc].Tm.rp; d.tci = L[lc].Tm.ci; d.tv = L[lc].Tm.v;
+            if (gh.ny > GJ_NB) dense_fallback = true;
+            voff += d.n;
+            woff += (long long)d.n * d.n;
+            boff += 5LL * d.nx * d.ny * d.ny;
+            aoff += (long long)d.n * (d.am + 1);
+            AMmax = std::max(AMmax, d.am);
+            maxnL = std::max(maxnL, d.n);
+            nxmax = std::max(nxmax, d.nx);
+            cdh.push_back(d);
+        }
+        if (dense_fallback && nch > 1) fail(BAMG_EUNSUPPORTED, "batched chains need coarsest grid sides <= %d", GJ_NB);
+        NVt = voff;
+        cd = A.upload(cdh);
+        Wp = A.alloc<double>(woff);
+        if (MIXED) Wfp = A.alloc<float>(woff);
+        Fp = A.alloc<double>(std::max<long long>(boff, 1));
+        for (double** p : {&ypool, &cpool, &bcolp, &t1, &t2, &rre, &rim}) *p = A.alloc<double>(NVt);
+        gtpart = A.alloc<double>((size_t)ceil_div(maxnL, GT_RCH) * NVt);
+        scale = A.alloc<double>(nch);
+        minpiv = A.alloc<double>(nch);
+        cy = A.alloc<double>(nch);
+        csc = A.alloc<double>((size_t)nch * SCS);
+        const int am = std::max(1, AMmax);
+        HS = (am + 1) * am;
+        HRS = am * am;
+        SS = 16 * 2 * am;
+        DS = am + 2;
+        Vb = A.alloc<double>(std::max<long long>(aoff, 1));
+        Hh = A.alloc<double>((size_t)nch * HS);
+        Hrow = A.alloc<double>((size_t)nch * HRS);
+        sel_lam = A.alloc<double>((size_t)nch * LSS);
+        sel_s = A.alloc<double>((size_t)nch * SS);
+        nsel = A.alloc<int>((size_t)nch * NS);
+        dots = A.alloc<double>((size_t)nch * DS);
+        lam = A.alloc<double>((size_t)nch * 2 * KV);
+        kind = A.alloc<int>((size_t)nch * KV);
+        ent_col = A.alloc<int>((size_t)nch * KV);
+        nvc = A.alloc<int>(nch);
+        nentc = A.alloc<int>(nch);
+        zero(nvc, sizeof(int) * nch);
+        zero(lam, sizeof(double) * nch * 2 * KV);
+        zero(kind, sizeof(int) * nch * KV);
+        zero(ent_col, sizeof(int) * nch * KV);
         x0 = A.alloc<double>(n);
         {
-            size_t need = std::max<size_t>((size_t)RED_PARTS * 2 * 64 + 4096,
-                                           (size_t)MDOT_BLOCKS * (BAMG_BLK / BAMG_WAVE) * (o.gmres_m + 2));
-            need = std::max<size_t>(need, (size_t)ceil_div(nL, GT_ROWS) * nL);
+            size_t need = 4096;
+            need = std::max(need, (size_t)nch * SEG_PARTS * 2 * WS);
+            need = std::max(need, (size_t)nch * SEG_PARTS * KV * 4);
+            need = std::max(need, (size_t)nch * MDOT_PARTS * (BAMG_BLK / BAMG_WAVE) * (o.gmres_m + 2));
             part = A.alloc<double>(need);
         }
-        sc = A.alloc<double>(64);
-        wts = A.alloc<double>(64);
+        sc = A.alloc<double>((size_t)nch * SCS);
+        wts = A.alloc<double>((size_t)nch * WS);
         err = A.alloc<int>(4);
         itmp = A.alloc<int>(n + 1);
         bsum = A.alloc<int>(nblk(n) + 1);
         total = A.alloc<int>(4);
-        const int am = std::max(1, std::min({o.arnoldi_m, nL - 1, HQR_MAXM}));
-        Vb = A.alloc<double>((size_t)nL * (am + 1));
-        Hh = A.alloc<double>((size_t)(am + 1) * am);
-        Hrow = A.alloc<double>((size_t)am * am);
-        sel_lam = A.alloc<double>(2 * 16);
-        sel_s = A.alloc<double>((size_t)16 * 2 * am);
-        ritz_re = A.alloc<double>(nL);
-        ritz_im = A.alloc<double>(nL);
-        nsel = A.alloc<int>(4);
-        ah = A.alloc<double>(HQR_MAXM + 8);
+        sweep_tmp = A.alloc<T>((size_t)n * std::max(r, VS));
     }
 
+    // Validate A and build B = I - A on the finest level.
     void build_b0(const int32_t* rp, const int32_t* ci, const double* val, int nnzA) {
         auto& lv = L[0];
-        GridDev gd = lv.g.dev();
         double* colsum = A.alloc<double>(n);
         zero(colsum, sizeof(double) * n);
         zero(err, sizeof(int) * 4);
-        LAUNCH(k_check_a, nblk(n), BAMG_BLK, s, (int)n, rp, ci, val, gd, nnzA, colsum, itmp, err);
+        LAUNCH(k_check_a, nblk(n), BAMG_BLK, s, (int)n, rp, ci, val, (const ChainGeo*)lv.dgeo, lv.nch, nnzA, colsum,
+               itmp, err);
         LAUNCH(k_check_colsum, nblk(n), BAMG_BLK, s, (int)n, colsum, err);
         int e = get1(err);
-        if (e & ERR_RANGE) fail(BAMG_EINVAL, "CSR of A: row_ptr not monotone, column out of range, or columns not strictly ascending");
+        if (e & ERR_RANGE)
+            fail(BAMG_EINVAL, "CSR of A: row_ptr not monotone, column out of range or outside its chain, or columns "
+                              "not strictly ascending");
         if (e & ERR_NEG) fail(BAMG_ENOTSTOCH, "A has a negative, non-finite or > 1 entry");
         if (e & ERR_COLSUM) fail(BAMG_ENOTSTOCH, "a column of A does not sum to 1 within 1e-12");
         if (e & ERR_WIDE) fail(BAMG_EUNSUPPORTED, "A joins states farther apart than the 3x3 grid box");
         scan((int)n, itmp, b0rp);
-        int nnzB = get1(b0rp + n);
-        nnz0 = nnzB;
+        nnz0 = get1(b0rp + n);
         T* lo = MIXED ? lv.B.v : nullptr;
         T* dlo = MIXED ? lv.dinv : nullptr;
         double* dinv64 = MIXED ? A.alloc<double>(n) : (double*)lv.dinv;
         LAUNCH(k_build_b<T>, nblk(n), BAMG_BLK, s, (int)n, rp, ci, val, b0rp, b0ci, b0v, lo, o.omega, dinv64, dlo, err);
         if (MIXED) {
             HIPCHK(hipMemcpyAsync(lv.B.rp, b0rp, sizeof(int) * (n + 1), hipMemcpyDeviceToDevice, s));
-            HIPCHK(hipMemcpyAsync(lv.B.ci, b0ci, sizeof(int) * nnzB, hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipMemcpyAsync(lv.B.ci, b0ci, sizeof(int) * nnz0, hipMemcpyDeviceToDevice, s));
         }
         e = get1(err);
         if (e & ERR_ZERODIAG) fail(BAMG_EZERODIAG, "b_ii <= 0 on the finest level");
     }
 
+    // -------------------------------------------------------------- setup steps
+    // nu homogeneous sweeps on the continuing rows of level l (R columns).
     void sweeps(int l, T* X, int R, int nu, bool profile) {
         auto& lv = L[l];
+        const int rows = lv.cont_rows;
+        if (rows == 0 || nu == 0) return;
         T* a = X;
         T* b = sweep_tmp;
         FastDiv dR((uint32_t)R);
-        long long tot = (long long)lv.n * R;
+        long long tot = (long long)rows * R;
         for (int k = 0; k < nu; ++k) {
             std::pair<hipEvent_t, hipEvent_t> ev;
             if (profile) ev = ev_begin();
-            LAUNCH((k_sweep<T, T>), nblk(tot), BAMG_BLK, s, lv.n, R, dR, lv.B.rp, lv.B.ci, lv.B.v, lv.dinv, a,
-                   (const T*)nullptr, b);
+            LAUNCH((k_sweep<T, T>), nblk(tot), BAMG_BLK, s, rows, R, dR, lv.B.rp, lv.B.ci, (const T*)lv.B.v,
+                   (const T*)lv.dinv, (const T*)a, (const T*)nullptr, b);
             if (profile) ev_end(ev, ev_sweep);
             std::swap(a, b);
         }
         if (a != X) HIPCHK(hipMemcpyAsync(X, a, sizeof(T) * tot, hipMemcpyDeviceToDevice, s));
     }
-    T* sweep_tmp = nullptr;
 
-    void tv_weights(int l, int Ru, int Rv, const T* U, const T* V) {
+    // TV weights of the continuing chains of level l.
+    void tv_weights(int l, int use_v) {
         auto& lv = L[l];
-        int R = Ru + Rv;
-        int bs = R * (BAMG_BLK / R);
-        int grid = RED_PARTS;
-        LAUNCH((k_colnorm_partial<T, T>), grid, bs, s, lv.n, Ru, Rv, FastDiv((uint32_t)R), lv.B.rp, lv.B.ci, lv.B.v,
-               U, V, part);
-        LAUNCH(k_colnorm_final, R, BAMG_BLK, s, grid, R, part, wts, (double*)nullptr);
+        dim3 grid(SEG_PARTS, lv.ncont);
+        hipLaunchKernelGGL((k_colnorm_partial<T, T>), grid, dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo, r, use_v,
+                           (const int*)nvc, VS, lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const T*)lv.U, (const T*)lv.V,
+                           WS, part);
+        HIPCHK(hipGetLastError());
+        dim3 g2(r + (use_v ? nvmax : 0), lv.ncont);
+        hipLaunchKernelGGL(k_colnorm_final, g2, dim3(BAMG_BLK), 0, s, SEG_PARTS, r, use_v, (const int*)nvc, WS,
+                           (const double*)part, wts);
+        HIPCHK(hipGetLastError());
     }
 
     void galerkin(int l, bool profile) {
         auto& f = L[l];
         auto& c = L[l + 1];
-        GridH cg = c.g;
-        FastDiv dcy((uint32_t)cg.ny);
-        int nc = c.n;
-        // B_{l+1} = Q (B P)
+        const int nc = c.rows;
+        const int gb = ceil_div(nc, GAL_ROWS);
         for (int which = 0; which < 2; ++which) {
             Csr<T>& M = which == 0 ? f.B : f.Tm;
-            Csr<T>& C = which == 0 ? c.B : c.Tm;
-            const int* mrp = M.rp;
-            const int gb = ceil_div(nc, GAL_ROWS);
-            LAUNCH(k_galerkin_symbolic, gb, GAL_THREADS, s, nc, dcy, cg.nx, cg.ny, cg.periodic, f.qc, mrp, M.ci,
-                   f.pc, f.cnt, f.mask);
-            scan(nc, f.cnt, C.rp);
+            Csr<T>& Cm = which == 0 ? c.B : c.Tm;
+            LAUNCH(k_galerkin_symbolic, gb, GAL_THREADS, s, nc, (const ChainGeo*)c.dgeo, c.nch, f.qc, M.rp, M.ci, f.pc,
+                   f.cnt, f.mask);
+            scan(nc, f.cnt, Cm.rp);
             std::pair<hipEvent_t, hipEvent_t> ev;
             if (profile) ev = ev_begin();
-            LAUNCH(k_galerkin_numeric<T>, gb, GAL_THREADS, s, nc, dcy, cg.nx, cg.ny, cg.periodic, f.qc,
-                   (const T*)f.qv, mrp, M.ci, (const T*)M.v, f.pc, (const T*)f.pv, f.mask, C.rp, C.ci, C.v);
+            LAUNCH(k_galerkin_numeric<T>, gb, GAL_THREADS, s, nc, (const ChainGeo*)c.dgeo, c.nch, f.qc, (const T*)f.qv,
+                   M.rp, M.ci, (const T*)M.v, f.pc, (const T*)f.pv, f.mask, Cm.rp, Cm.ci, Cm.v);
             if (profile) ev_end(ev, ev_gal);
         }
         zero(err, sizeof(int) * 4);
         LAUNCH(k_dinv<T>, nblk(nc), BAMG_BLK, s, nc, c.B.rp, c.B.ci, c.B.v, o.omega, c.dinv, err);
     }
 
-    void build_level(int l, int Ru, int Rv, const T* U, const T* V, T* inject, bool profile) {
+    void build_level(int l, int use_v, bool inject, bool profile) {
         auto& lv = L[l];
         auto& c = L[l + 1];
-        tv_weights(l, Ru, Rv, U, V);
+        if (lv.ncont == 0) return;
+        tv_weights(l, use_v);
         std::pair<hipEvent_t, hipEvent_t> ev;
         if (profile) ev = ev_begin();
-        LAUNCH((k_ls_fit<T, T>), nblk(lv.n), BAMG_BLK, s, lv.n, lv.g.dev(), c.g.ny, Ru, Rv, U, V, (const double*)wts,
-               o.caliber, lv.pc, lv.pv, inject, (int*)nullptr);
+        LAUNCH((k_ls_fit<T, T>), nblk(lv.cont_rows), BAMG_BLK, s, lv.cont_rows, (const ChainGeo*)lv.dgeo, lv.ncont, r,
+               use_v, (const int*)nvc, VS, (const T*)lv.U, (const T*)lv.V, (const double*)wts, WS, o.caliber, lv.pc,
+               lv.pv, inject ? c.U : (T*)nullptr, (int*)nullptr);
         if (profile) ev_end(ev, ev_ls);
-        LAUNCH(k_build_q<T>, nblk(c.n), BAMG_BLK, s, c.n, lv.g.dev(), FastDiv((uint32_t)c.g.ny), c.g.ny, lv.pc, lv.qc,
-               lv.qv);
+        LAUNCH(k_build_q<T>, nblk(c.rows), BAMG_BLK, s, c.rows, (const ChainGeo*)c.dgeo, (const ChainGeo*)lv.dgeo, c.nch,
+               lv.pc, lv.qc, lv.qv);
         galerkin(l, profile);
     }
 
-    // Inverse of the padded coarsest operator [[B_11, 0], [0, 1]] into W by
-    // block LU of its block-tridiagonal (+ periodic corner) structure; the
-    // dense B_L is in W on entry.  Grid rows give blocks of b = ny <= 64.
-    double* btbuf = nullptr;
-    void block_tridiagonal_inverse(const GridH& g) {
-        const int nx = g.nx, b = g.ny, K = nx - 1, bb = b * b;
-        const bool arrow = g.periodic && nx >= 3;
-        if (!btbuf) btbuf = A.alloc<double>((size_t)5 * nx * bb);
-        double* Dk = btbuf;
-        double* Up = Dk + (size_t)nx * bb;
-        double* Lo = Up + (size_t)nx * bb;
-        double* Cl = Lo + (size_t)nx * bb;
-        double* Rw = Cl + (size_t)nx * bb;
-        {
-            dim3 grid(ceil_div(bb, BAMG_BLK), nx, arrow ? 5 : 3);
-            hipLaunchKernelGGL(k_bt_extract, grid, dim3(BAMG_BLK), 0, s, nx, b, (const double*)W, Dk, Up, Lo, Cl, Rw);
-            HIPCHK(hipGetLastError());
-        }
-        auto blk = [&](double* base, int k) { return base + (size_t)k * bb; };
-        auto inv = [&](int k) {
-            LAUNCH(k_gj_diag, 1, BAMG_BLK, s, b, 0, b, blk(Dk, k), (const double*)(sc + 10), sc + 11);
-        };
-        for (int k = 0; k < K; ++k) {
-            inv(k);
-            BlkOps g1{}, g2{};
-            if (k + 1 < K) {
-                int q = 0;
-                g1.A[q] = blk(Lo, k + 1); g1.B[q] = blk(Dk, k); g1.C[q] = blk(Lo, k + 1); g1.mode[q++] = 0;
-                if (arrow) { g1.A[q] = blk(Rw, k); g1.B[q] = blk(Dk, k); g1.C[q] = blk(Rw, k); g1.mode[q++] = 0; }
-                LAUNCH(k_blk_gemm, q, BAMG_BLK, s, b, g1);
-                q = 0;
-                g2.A[q] = blk(Lo, k + 1); g2.B[q] = blk(Up, k); g2.C[q] = blk(Dk, k + 1); g2.mode[q++] = 1;
-                if (arrow) {
-                    double* colK = (k + 1 < K - 1) ? blk(Cl, k + 1) : blk(Up, k + 1);
-                    double* rowK = (k + 1 < K - 1) ? blk(Rw, k + 1) : blk(Lo, K);
-                    g2.A[q] = blk(Lo, k + 1); g2.B[q] = blk(Cl, k); g2.C[q] = colK; g2.mode[q++] = 1;
-                    g2.A[q] = blk(Rw, k); g2.B[q] = blk(Up, k); g2.C[q] = rowK; g2.mode[q++] = 1;
-                    g2.A[q] = blk(Rw, k); g2.B[q] = blk(Cl, k); g2.C[q] = blk(Dk, K); g2.mode[q++] = 1;
-                }
-                LAUNCH(k_blk_gemm, q, BAMG_BLK, s, b, g2);
-            } else {
-                g1.A[0] = blk(Lo, K); g1.B[0] = blk(Dk, k); g1.C[0] = blk(Lo, K); g1.mode[0] = 0;
-                LAUNCH(k_blk_gemm, 1, BAMG_BLK, s, b, g1);
-                g2.A[0] = blk(Lo, K); g2.B[0] = blk(Up, k); g2.C[0] = blk(Dk, K); g2.mode[0] = 1;
-                LAUNCH(k_blk_gemm, 1, BAMG_BLK, s, b, g2);
-            }
-        }
-        inv(K);
-        // forward substitution on the identity: W[k] = E_k - sum L_kj W[j]
-        const long long nn = (long long)nL * nL;
-        LAUNCH(k_identity, nblk(nn), BAMG_BLK, s, nn, nL, W);
-        const int ct = ceil_div(nL, 64);
-        for (int k = 1; k < K; ++k)
-            LAUNCH(k_bt_strip, ct, BAMG_BLK, s, b, nL, W, k, (const double*)blk(Lo, k), k - 1, (const double*)nullptr,
-                   0, (const double*)nullptr);
-        if (K >= 1) {
-            if (arrow)
-                for (int j = 0; j < K - 1; j += 2) {
-                    const double* A2 = j + 1 < K - 1 ? blk(Rw, j + 1) : nullptr;
-                    LAUNCH(k_bt_strip, ct, BAMG_BLK, s, b, nL, W, K, (const double*)blk(Rw, j), j, A2, j + 1,
-                           (const double*)nullptr);
-                }
-            LAUNCH(k_bt_strip, ct, BAMG_BLK, s, b, nL, W, K, (const double*)blk(Lo, K), K - 1, (const double*)nullptr,
-                   0, (const double*)nullptr);
-        }
-        // back substitution: W[k] = Dinv_k (W[k] - U_k W[k+1] - C_k W[K])
-        LAUNCH(k_bt_strip, ct, BAMG_BLK, s, b, nL, W, K, (const double*)nullptr, 0, (const double*)nullptr, 0,
-               (const double*)blk(Dk, K));
-        for (int k = K - 1; k >= 0; --k) {
-            const double* A2 = (arrow && k < K - 1) ? blk(Cl, k) : nullptr;
-            LAUNCH(k_bt_strip, ct, BAMG_BLK, s, b, nL, W, k, (const double*)blk(Up, k), k + 1, A2, K,
-                   (const double*)blk(Dk, k));
-        }
-    }
-
-    // Dense pseudo-inverse of the coarsest operator into W, null vector y.
+    // ---- coarsest pseudo-inverses of every chain into the W pool ------------
     void coarsest_inverse() {
-        auto& cl = L.back();
-        const int m = nL - 1;
-        const long long nn = (long long)nL * nL;
-        LAUNCH(k_fill, nblk(nn), BAMG_BLK, s, nn, 0.0, W);
-        LAUNCH(k_densify_cast<T>, nblk(nL), BAMG_BLK, s, nL, cl.B.rp, cl.B.ci, cl.B.v, W);
-        LAUNCH(k_get_col, nblk(nL), BAMG_BLK, s, nL, nL, nL - 1, W, bcol);
-        LAUNCH(k_absmax_partial, 64, BAMG_BLK, s, nn, W, part);
-        LAUNCH(k_absmax_partial, 1, BAMG_BLK, s, 64LL, part, sc + 10);
-        double big = 1e300;
-        HIPCHK(hipMemcpyAsync(sc + 11, &big, sizeof(double), hipMemcpyHostToDevice, s));
-        if (m > 0) {
-            if (cl.g.ny <= GJ_NB) {
-                block_tridiagonal_inverse(cl.g);
-            } else {
-                const int tiles = ceil_div(m, 64);
-                const int ut = ceil_div(m, GJ_T);
-                for (int k0 = 0; k0 < m; k0 += GJ_NB) {
-                    int nb = std::min(GJ_NB, m - k0);
-                    LAUNCH(k_gj_diag, 1, BAMG_BLK, s, nL, k0, nb, W, (const double*)(sc + 10), sc + 11);
-                    LAUNCH(k_gj_rowpanel, tiles, BAMG_BLK, s, m, nL, k0, nb, W);
-                    LAUNCH(k_gj_update, ut * ut, BAMG_BLK, s, m, nL, k0, nb, W);
-                    LAUNCH(k_gj_colpanel, tiles, BAMG_BLK, s, m, nL, k0, nb, W);
-                }
-            }
-        }
-        LAUNCH(k_zero_border, nblk(nL), BAMG_BLK, s, nL, W);
-        // y = [-Binv b_col; 1]
-        if (m > 0) LAUNCH(k_gemv, ceil_div(m, 4), BAMG_BLK, s, m, m, nL, (const double*)W, (const double*)bcol, tmpL);
-        LAUNCH(k_null_finish, nblk(nL), BAMG_BLK, s, nL, (const double*)tmpL, y);
-        // projections: s = W 1, u = y^T W, sc0 = y^T s, sc1 = y^T y
-        LAUNCH(k_fill, nblk(nL), BAMG_BLK, s, (long long)nL, 1.0, tmpL2);
-        LAUNCH(k_gemv, ceil_div(nL, 4), BAMG_BLK, s, nL, nL, nL, (const double*)W, (const double*)tmpL2, tmpL);
+        long long wtot = 0;
+        for (auto& d : cdh) wtot += (long long)d.n * d.n;
+        LAUNCH(k_fill, nblk(wtot), BAMG_BLK, s, wtot, 0.0, Wp);
+        // b_col keeps only the stored entries of the last column: clear it
+        LAUNCH(k_fill, nblk(NVt), BAMG_BLK, s, (long long)NVt, 0.0, bcolp);
+        const dim3 gv(nblk(maxnL), nch);
+        hipLaunchKernelGGL(k_cz_densify<T>, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, Wp, bcolp);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_cz_absmax, dim3(1, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, (const double*)Wp,
+                           scale);
+        HIPCHK(hipGetLastError());
         {
-            dim3 gt(nblk(nL), ceil_div(nL, GT_ROWS));
-            hipLaunchKernelGGL(k_gemv_t_partial, gt, dim3(BAMG_BLK), 0, s, nL, nL, nL, (const double*)W,
-                               (const double*)y, part);
-            HIPCHK(hipGetLastError());
-            LAUNCH(k_gemv_t_final, nblk(nL), BAMG_BLK, s, (int)gt.y, nL, (const double*)part, tmpL2);
+            std::vector<double> big(nch, 1e300);
+            HIPCHK(hipMemcpyAsync(minpiv, big.data(), sizeof(double) * nch, hipMemcpyHostToDevice, s));
+            sync();
         }
-        LAUNCH(k_dot1, 1, BAMG_BLK, s, nL, (const double*)y, (const double*)tmpL, sc + 0);
-        LAUNCH(k_dot1, 1, BAMG_BLK, s, nL, (const double*)y, (const double*)y, sc + 1);
-        LAUNCH(k_project_w, nblk(nn), BAMG_BLK, s, nL, W, (const double*)tmpL, (const double*)tmpL2, (const double*)y,
-               (const double*)sc);
+        if (dense_fallback) {
+            dense_gj_inverse();
+        } else {
+            int bbmax = 0;
+            for (auto& d : cdh) bbmax = std::max(bbmax, d.ny * d.ny);
+            hipLaunchKernelGGL(k_cz_extract, dim3(nblk(bbmax), nxmax, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd,
+                               (const double*)Wp, Fp);
+            HIPCHK(hipGetLastError());
+            for (int k = 0; k + 1 < nxmax; ++k) {
+                LAUNCH(k_cz_diag, nch, BAMG_BLK, s, (const CoarseDesc*)cd, k, Fp, (const double*)scale, minpiv);
+                hipLaunchKernelGGL(k_cz_elim, dim3(4, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, k, 0, Fp);
+                hipLaunchKernelGGL(k_cz_elim, dim3(4, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, k, 1, Fp);
+                HIPCHK(hipGetLastError());
+            }
+            LAUNCH(k_cz_diag, nch, BAMG_BLK, s, (const CoarseDesc*)cd, -1, Fp, (const double*)scale, minpiv);
+            hipLaunchKernelGGL(k_cz_identity, dim3(nblk((long long)maxnL * maxnL), nch), dim3(BAMG_BLK), 0, s,
+                               (const CoarseDesc*)cd, Wp);
+            const dim3 gs(ceil_div(maxnL, 64), nch);
+            for (int stp = 1; stp + 1 < nxmax; ++stp)
+                hipLaunchKernelGGL(k_cz_strip, gs, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, 0, stp, Wp,
+                                   (const double*)Fp);
+            for (int stp = 0; 2 * stp < nxmax - 2; ++stp)
+                hipLaunchKernelGGL(k_cz_strip, gs, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, 1, stp, Wp,
+                                   (const double*)Fp);
+            hipLaunchKernelGGL(k_cz_strip, gs, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, 2, 0, Wp, (const double*)Fp);
+            hipLaunchKernelGGL(k_cz_strip, gs, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, 3, 0, Wp, (const double*)Fp);
+            for (int stp = 0; stp < nxmax - 1; ++stp)
+                hipLaunchKernelGGL(k_cz_strip, gs, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, 4, stp, Wp,
+                                   (const double*)Fp);
+            HIPCHK(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_cz_zero_border, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, Wp);
+        // y = [-Binv b_col; 1]
+        const dim3 gw(ceil_div(maxnL, 4), nch);
+        hipLaunchKernelGGL(k_cz_gemv, gw, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, 1, (const double*)Wp,
+                           (const double*)bcolp, t1);
+        hipLaunchKernelGGL(k_cz_null, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, (const double*)t1, ypool);
+        // s = W 1, u = y^T W, y^T s, y^T y, projections
+        LAUNCH(k_fill, nblk(NVt), BAMG_BLK, s, (long long)NVt, 1.0, t2);
+        hipLaunchKernelGGL(k_cz_gemv, gw, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, 0, (const double*)Wp,
+                           (const double*)t2, t1);
+        {
+            const int nchunk = ceil_div(maxnL, GT_RCH);
+            hipLaunchKernelGGL(k_cz_gemv_t_partial, dim3(nblk(maxnL), nchunk, nch), dim3(BAMG_BLK), 0, s,
+                               (const CoarseDesc*)cd, (const double*)Wp, (const double*)ypool, gtpart, GT_RCH);
+            hipLaunchKernelGGL(k_cz_gemv_t_final, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, nchunk, GT_RCH,
+                               (const double*)gtpart, t2);
+        }
+        LAUNCH(k_cz_dot, nch, BAMG_BLK, s, (const CoarseDesc*)cd, (const double*)ypool, (const double*)t1, csc, SCS);
+        LAUNCH(k_cz_dot, nch, BAMG_BLK, s, (const CoarseDesc*)cd, (const double*)ypool, (const double*)ypool, csc + 1,
+               SCS);
+        hipLaunchKernelGGL(k_cz_project, dim3(nblk((long long)maxnL * maxnL), nch), dim3(BAMG_BLK), 0, s,
+                           (const CoarseDesc*)cd, Wp, (const double*)t1, (const double*)t2, (const double*)ypool,
+                           (const double*)csc, SCS);
         // c = T^T 1, cy = c^T y
-        LAUNCH(k_colsum_box<T>, nblk(nL), BAMG_BLK, s, nL, FastDiv((uint32_t)cl.g.ny), cl.g.nx, cl.g.ny,
-               cl.g.periodic, cl.Tm.rp, cl.Tm.ci, (const T*)cl.Tm.v, cvec);
-        LAUNCH(k_dot1, 1, BAMG_BLK, s, nL, (const double*)cvec, (const double*)y, sc + 2);
-        st.coarsest_min_pivot = get1(sc + 11);
-        if (m > 0 && !(st.coarsest_min_pivot > 1e-12))
-            fail(BAMG_ESINGULAR, "coarsest pivot %.3e below 1e-12 of max |B_L|", st.coarsest_min_pivot);
-        if (MIXED) LAUNCH((k_cast<double, float>), nblk(nn), BAMG_BLK, s, nn, (const double*)W, Wf);
+        hipLaunchKernelGGL(k_cz_colsum<T>, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, cpool);
+        LAUNCH(k_cz_dot, nch, BAMG_BLK, s, (const CoarseDesc*)cd, (const double*)cpool, (const double*)ypool, cy, 1);
+        std::vector<double> mp = getn(minpiv, nch);
+        double mn = 1e300;
+        for (double v : mp) mn = std::min(mn, v);
+        st.coarsest_min_pivot = mn;
+        if (!(mn > 1e-12)) fail(BAMG_ESINGULAR, "coarsest pivot %.3e below 1e-12 of max |B_L|", mn);
+        if (MIXED) LAUNCH((k_cast<double, float>), nblk(wtot), BAMG_BLK, s, wtot, (const double*)Wp, Wfp);
     }
 
-    // Coarsest eigenpairs (Algorithm 3, l = L) by Arnoldi on the shift-invert
-    // operator; fills V_L, lam, kind, ent_col and nv.
-    void coarsest_eigs() {
-        auto& cl = L.back();
-        const int want = o.n_eig - 1;
-        int am = std::min({o.arnoldi_m, nL - 1, HQR_MAXM});
-        int ne = 0, ncols = 0;
-        if (want > 0 && am >= 1) {
-            zero(Hh, sizeof(double) * (am + 1) * am);
-            LAUNCH(k_rand_vec, nblk(nL), BAMG_BLK, s, nL, o.seed, Vb);
-            LAUNCH(k_dot1, 1, BAMG_BLK, s, nL, (const double*)cvec, (const double*)Vb, sc + 3);
-            LAUNCH(k_project_domain, nblk(nL), BAMG_BLK, s, nL, (const double*)y, (const double*)(sc + 3),
-                   (const double*)(sc + 2), Vb);
-            LAUNCH(k_dot1, 1, BAMG_BLK, s, nL, (const double*)Vb, (const double*)Vb, sc + 4);
-            LAUNCH(k_normalize_into, nblk(nL), BAMG_BLK, s, nL, (const double*)Vb, (const double*)(sc + 4), Vb, sc + 5);
-            for (int j = 0; j < am; ++j) {
-                double* vj = Vb + (size_t)j * nL;
-                // w = T v_j
-                if (cl.Tm.rp) {
-                    LAUNCH(k_spmv<T>, nblk(nL), BAMG_BLK, s, nL, cl.Tm.rp, cl.Tm.ci, (const T*)cl.Tm.v,
-                           (const double*)vj, 1.0, tmpL);
-                } else {
-                    LAUNCH(k_copy, nblk(nL), BAMG_BLK, s, (long long)nL, (const double*)vj, tmpL);
-                }
-                double* u = Vb + (size_t)(j + 1) * nL;
-                LAUNCH(k_gemv, ceil_div(nL, 4), BAMG_BLK, s, nL, nL, nL, (const double*)W, (const double*)tmpL, u);
-                LAUNCH(k_dot1, 1, BAMG_BLK, s, nL, (const double*)cvec, (const double*)u, sc + 3);
-                LAUNCH(k_project_domain, nblk(nL), BAMG_BLK, s, nL, (const double*)y, (const double*)(sc + 3),
-                       (const double*)(sc + 2), u);
-                double* hcol = Hh + (size_t)j * (am + 1);
-                for (int pass = 0; pass < 2; ++pass) {
-                    LAUNCH(k_mdot, j + 1, BAMG_BLK, s, nL, j + 1, (const double*)Vb, (const double*)u, ah);
-                    LAUNCH(k_mupdate, nblk(nL), BAMG_BLK, s, nL, j + 1, (const double*)Vb, (const double*)ah, u,
-                           hcol);
-                }
-                LAUNCH(k_dot1, 1, BAMG_BLK, s, nL, (const double*)u, (const double*)u, sc + 4);
-                LAUNCH(k_normalize_into, nblk(nL), BAMG_BLK, s, nL, (const double*)u, (const double*)(sc + 4), u,
-                       hcol + j + 1);
+    // Dense blocked Gauss-Jordan (coarse sides > 64; single chain only).
+    void dense_gj_inverse() {
+        const CoarseDesc& d = cdh[0];
+        const int nL = d.n, m = nL - 1;
+        if (m <= 0) return;
+        const int tiles = ceil_div(m, 64);
+        const int ut = ceil_div(m, GJ_T);
+        for (int k0 = 0; k0 < m; k0 += GJ_NB) {
+            int nb = std::min(GJ_NB, m - k0);
+            LAUNCH(k_gj_diag, 1, BAMG_BLK, s, nL, k0, nb, Wp, (const double*)scale, minpiv);
+            LAUNCH(k_gj_rowpanel, tiles, BAMG_BLK, s, m, nL, k0, nb, Wp);
+            LAUNCH(k_gj_update, ut * ut, BAMG_BLK, s, m, nL, k0, nb, Wp);
+            LAUNCH(k_gj_colpanel, tiles, BAMG_BLK, s, m, nL, k0, nb, Wp);
+        }
+    }
+
+    // u (column j+1 of every chain's basis): u -= y (c^T u)/cy, two rounds
+    // of classical Gram-Schmidt against columns 0..j, normalise (H[j+1, j]).
+    void project_and_normalize(int j) {
+        const dim3 gv(nblk(maxnL), nch);
+        hipLaunchKernelGGL(k_cz_arn_dots, dim3(1, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, 1,
+                           (const double*)cpool, (const double*)Vb, dots, DS);
+        hipLaunchKernelGGL(k_cz_arn_update, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, 0, (const double*)ypool,
+                           (const double*)cy, (const double*)dots, DS, Vb, Hh, HS);
+        if (j >= 0) {
+            for (int pass = 0; pass < 2; ++pass) {
+                hipLaunchKernelGGL(k_cz_arn_dots, dim3(j + 1, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, 0,
+                                   (const double*)cpool, (const double*)Vb, dots, DS);
+                hipLaunchKernelGGL(k_cz_arn_update, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, 1,
+                                   (const double*)ypool, (const double*)cy, (const double*)dots, DS, Vb, Hh, HS);
             }
-            LAUNCH(k_hessenberg_eig, 1, BAMG_WAVE, s, am, want, (const double*)Hh, Hrow, nsel, sel_lam, sel_s);
-            int h[4];
-            HIPCHK(hipMemcpyAsync(h, nsel, sizeof(int) * 3, hipMemcpyDeviceToHost, s));
-            sync();
-            if (h[2]) fail(BAMG_EDEVICE, "Hessenberg QR of the coarsest Arnoldi matrix did not converge");
-            ne = h[0];
-            ncols = h[1];
         }
-        nv = 1 + ncols;
-        nent = 1 + ne;
-        // V_L: column 0 = y / (c^T y), then normalised Ritz vectors
-        double* VL = MIXED ? A.alloc<double>((size_t)nL * nv) : (double*)cl.V;
-        LAUNCH(k_scale_into_col, nblk(nL), BAMG_BLK, s, nL, (const double*)y, (const double*)(sc + 2), VL, nv, 0);
-        std::vector<double> hl(2 * 16);
-        int col = 1;
-        if (ne > 0) {
-            HIPCHK(hipMemcpyAsync(hl.data(), sel_lam, sizeof(double) * 2 * ne, hipMemcpyDeviceToHost, s));
-            sync();
+        HIPCHK(hipGetLastError());
+        LAUNCH(k_cz_arn_normalize, nch, BAMG_BLK, s, (const CoarseDesc*)cd, j, Vb, Hh, HS);
+    }
+
+    // ---- coarsest eigenpairs (Arnoldi, all chains in lockstep) ---------------
+    void coarsest_eigs() {
+        const int want = o.n_eig - 1;
+        const dim3 gv(nblk(maxnL), nch);
+        const dim3 gw(ceil_div(maxnL, 4), nch);
+        if (want > 0 && AMmax >= 1) {
+            zero(Hh, sizeof(double) * nch * HS);
+            hipLaunchKernelGGL(k_cz_arn_start, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, o.seed, Vb);
+            HIPCHK(hipGetLastError());
+            // the start vector is basis column 0: project and normalise it as
+            // "column j + 1" with j = -1 (no H entry)
+            project_and_normalize(-1);
+            for (int j = 0; j < AMmax; ++j) {
+                hipLaunchKernelGGL(k_cz_tv<T>, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, (const double*)Vb, t1);
+                hipLaunchKernelGGL(k_cz_arn_gemv, gw, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, (const double*)Wp,
+                                   (const double*)t1, Vb);
+                HIPCHK(hipGetLastError());
+                project_and_normalize(j);
+            }
         }
-        for (int e = 0; e < ne; ++e) {
-            bool pair = hl[2 * e + 1] != 0.0;
-            LAUNCH(k_ritz, nblk(nL), BAMG_BLK, s, nL, am, (const double*)Vb, (const double*)(sel_s + (size_t)e * 2 * am),
-                   ritz_re, ritz_im);
-            LAUNCH(k_eigvec_normalise, 1, BAMG_BLK, s, nL, (const double*)ritz_re, (const double*)ritz_im, pair ? 1 : 0,
-                   VL, nv, col);
-            col += pair ? 2 : 1;
+        LAUNCH(k_cz_hess, nch, BAMG_WAVE, s, (const CoarseDesc*)cd, want, (const double*)Hh, HS, Hrow, HRS, nsel, NS,
+               sel_lam, LSS, sel_s, SS);
+        std::vector<int> hs = getn(nsel, (size_t)nch * NS);
+        int emax = 0;
+        for (int c = 0; c < nch; ++c) {
+            if (hs[(size_t)c * NS + 2]) fail(BAMG_EDEVICE, "Hessenberg QR of chain %d's coarsest Arnoldi matrix failed", c);
+            emax = std::max(emax, hs[(size_t)c * NS]);
         }
-        LAUNCH(k_eig_tables, 1, 64, s, (const int*)nsel, (const double*)sel_lam, lam, kind, ent_col);
-        if (ne == 0) {
-            // no nonzero eigenpairs requested or available: only the null vector
-            std::vector<double> z(4, 0.0);
-            std::vector<int> kz(2, 0);
-            HIPCHK(hipMemcpyAsync(lam, z.data(), sizeof(double) * 2, hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(kind, kz.data(), sizeof(int), hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(ent_col, kz.data(), sizeof(int), hipMemcpyHostToDevice, s));
+        LAUNCH(k_cz_tables, ceil_div(nch, 64), 64, s, nch, (const int*)nsel, NS, (const double*)sel_lam, LSS, lam, kind,
+               ent_col, KV, nvc, nentc);
+        nvc_h = getn(nvc, nch);
+        nvmax = 1;
+        for (int v : nvc_h) nvmax = std::max(nvmax, v);
+        if (nvmax > VS) fail(BAMG_EDEVICE, "eigenvector columns exceed the reserved %d", VS);
+        // every chain's coarsest rows live on its own level: one launch per level
+        for (int l = 0; l < (int)L.size(); ++l) {
+            auto& lv = L[l];
+            const int c0 = lv.ncont, c1 = lv.nch;          // chains whose coarsest level is l
+            if (c1 <= c0) continue;
+            const CoarseDesc* cdl = cd + c0;
+            const dim3 gvl(nblk(maxnL), c1 - c0);
+            hipLaunchKernelGGL(k_cz_ycol<T>, gvl, dim3(BAMG_BLK), 0, s, cdl, (const double*)ypool,
+                               (const double*)(cy + c0), lv.V, VS);
+            for (int e = 0; e < emax; ++e) {
+                hipLaunchKernelGGL(k_cz_ritz, gvl, dim3(BAMG_BLK), 0, s, cdl, e, (const int*)(nsel + (size_t)c0 * NS), NS,
+                                   (const double*)Vb, (const double*)(sel_s + (size_t)c0 * SS), SS, rre, rim);
+                hipLaunchKernelGGL(k_cz_eigvec<T>, dim3(c1 - c0), dim3(BAMG_BLK), 0, s, cdl, e,
+                                   (const int*)(nsel + (size_t)c0 * NS), NS, (const double*)(sel_lam + (size_t)c0 * LSS),
+                                   LSS, (const double*)rre, (const double*)rim, (const int*)(ent_col + (size_t)c0 * KV),
+                                   KV, lv.V, VS);
+            }
+            HIPCHK(hipGetLastError());
         }
-        if (MIXED) LAUNCH((k_cast<double, float>), nblk((long long)nL * nv), BAMG_BLK, s, (long long)nL * nv,
-                          (const double*)VL, (float*)cl.V);
     }
 
     void upleg() {
         for (int l = (int)L.size() - 2; l >= 0; --l) {
             auto& lv = L[l];
             auto& c = L[l + 1];
-            long long tot = (long long)lv.n * nv;
-            FastDiv dR((uint32_t)nv);
-            LAUNCH((k_interp<T, T>), nblk(tot), BAMG_BLK, s, lv.n, nv, dR, lv.pc, (const T*)lv.pv, (const T*)c.V, lv.V);
+            if (lv.ncont == 0) continue;
+            const int rows = lv.cont_rows;
+            long long tot = (long long)rows * VS;
+            FastDiv dR((uint32_t)VS);
+            LAUNCH((k_interp<T, T>), nblk(tot), BAMG_BLK, s, rows, VS, dR, lv.pc, (const T*)lv.pv, (const T*)c.V, lv.V);
             T* a = lv.V;
             T* b = sweep_tmp;
             for (int k = 0; k < o.nu_setup; ++k) {
-                LAUNCH((k_eig_relax<T, T>), nblk(lv.n), BAMG_BLK, s, lv.n, nv, lv.B.rp, lv.B.ci, (const T*)lv.B.v,
-                       lv.Tm.rp, lv.Tm.ci, (const T*)lv.Tm.v, (const double*)lam, (const int*)kind, o.omega,
-                       (const T*)a, b);
+                LAUNCH((k_eig_relax<T, T>), nblk(rows), BAMG_BLK, s, rows, (const ChainGeo*)lv.dgeo, lv.ncont, VS,
+                       (const int*)nvc, KV, lv.B.rp, lv.B.ci, (const T*)lv.B.v, lv.Tm.rp, lv.Tm.ci, (const T*)lv.Tm.v,
+                       (const double*)lam, (const int*)kind, o.omega, (const T*)a, b);
                 std::swap(a, b);
             }
             if (a != lv.V) HIPCHK(hipMemcpyAsync(lv.V, a, sizeof(T) * tot, hipMemcpyDeviceToDevice, s));
-            if (nent > 1) {
-                const int grid = 256;
-                LAUNCH((k_rayleigh_partial<T, T>), grid, BAMG_BLK, s, lv.n, nv, nent, (const int*)ent_col,
-                       (const int*)kind, lv.B.rp, lv.B.ci, (const T*)lv.B.v, lv.Tm.rp, lv.Tm.ci, (const T*)lv.Tm.v,
-                       (const T*)lv.V, part);
-                LAUNCH(k_rayleigh_final, nent, BAMG_BLK, s, grid, nent, (const int*)ent_col, (const int*)kind,
-                       (const double*)part, lam);
+            if (nvmax > 1) {
+                hipLaunchKernelGGL((k_rayleigh_partial<T, T>), dim3(SEG_PARTS, lv.ncont), dim3(BAMG_BLK), 0, s,
+                                   (const ChainGeo*)lv.dgeo, VS, KV, (const int*)nentc, (const int*)ent_col,
+                                   (const int*)kind, lv.B.rp, lv.B.ci, (const T*)lv.B.v, lv.Tm.rp, lv.Tm.ci,
+                                   (const T*)lv.Tm.v, (const T*)lv.V, part);
+                hipLaunchKernelGGL(k_rayleigh_final, dim3(KV, lv.ncont), dim3(BAMG_BLK), 0, s, SEG_PARTS, KV,
+                                   (const int*)nentc, (const int*)ent_col, (const int*)kind, (const double*)part, lam);
+                HIPCHK(hipGetLastError());
             }
         }
-        // x0 = V_0[:, 0] / sum
-        auto& l0 = L[0];
-        extract_col0(l0.V, nv, x0);
-        reduce<RED_SUM>(n, x0, nullptr, sc + 7);
-        LAUNCH(k_scale, nblk(n), BAMG_BLK, s, (int)n, (const double*)x0, (const double*)nullptr,
-               (const double*)(sc + 7), 0, x0);
+        // x0 = V_0[:, 0] / sum per chain
+        LAUNCH((k_get_col_t<T>), nblk(n), BAMG_BLK, s, (int)n, VS, 0, (const T*)L[0].V, x0);
+        seg_reduce<RED_SUM>(x0, nullptr, sc);
+        LAUNCH(k_seg_scale, nblk(n), BAMG_BLK, s, (int)n, (const ChainGeo*)L[0].dgeo, nch, (const int*)nullptr,
+               (const double*)x0, (const double*)nullptr, (const double*)sc, SCS, 0, x0);
     }
 
-    void extract_col0(const T* V, int R, double* out) {
-        LAUNCH((k_get_col_t<T>), nblk(n), BAMG_BLK, s, (int)n, R, 0, V, out);
+    void reorder_input(const int32_t*& rp, const int32_t*& ci, const double*& val, int nnzA) {
+        // caller order -> depth order (block-diagonal: columns shift with rows)
+        std::vector<int> so(nch), dof(nch), ln(nch);
+        for (int c = 0; c < nch; ++c) {
+            so[c] = (int)chains[c].uoff;
+            dof[c] = L[0].geo[c].off;
+            ln[c] = (int)chains[c].n;
+        }
+        perm_src = A.upload(so);
+        perm_dst = A.upload(dof);
+        perm_len = A.upload(ln);
+        reordered = false;
+        for (int c = 0; c < nch; ++c) reordered |= so[c] != dof[c];
+        if (!reordered) return;
+        zero(err, sizeof(int) * 4);
+        LAUNCH(k_check_rp, nblk(n), BAMG_BLK, s, (int)n, rp, nnzA, err);
+        if (get1(err) & ERR_RANGE) fail(BAMG_EINVAL, "CSR of A: row_ptr not monotone or outside [0, nnz]");
+        int maxn = *std::max_element(ln.begin(), ln.end());
+        int* cnt = A.alloc<int>(n + 1);
+        int* nrp = A.alloc<int>(n + 1);
+        hipLaunchKernelGGL(k_seg_csr_len, dim3(nblk(maxn), nch), dim3(BAMG_BLK), 0, s, nch, (const int*)perm_src,
+                           (const int*)perm_dst, (const int*)perm_len, rp, cnt);
+        HIPCHK(hipGetLastError());
+        scan((int)n, cnt, nrp);
+        if (get1(nrp + n) != nnzA) fail(BAMG_EINVAL, "row_ptr does not describe the concatenated chains");
+        int* nci = A.alloc<int>(nnzA);
+        double* nvv = A.alloc<double>(nnzA);
+        hipLaunchKernelGGL(k_seg_csr_fill, dim3(nblk(maxn), nch), dim3(BAMG_BLK), 0, s, (const int*)perm_src,
+                           (const int*)perm_dst, (const int*)perm_len, rp, ci, val, (const int*)nrp, nci, nvv);
+        HIPCHK(hipGetLastError());
+        rp = nrp; ci = nci; val = nvv;
     }
 
     void setup(const int32_t* rp, const int32_t* ci, const double* val) override {
         auto t0 = std::chrono::steady_clock::now();
         A.s = s;
         A.budget = o.mem_budget;
-        plan = level_plan(grid, o.levels, o.coarse_max);
         int hr[2];
         HIPCHK(hipMemcpyAsync(&hr[0], rp, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(&hr[1], rp + n, sizeof(int), hipMemcpyDeviceToHost, s));
         sync();
         if (hr[0] != 0 || hr[1] < 0) fail(BAMG_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] >= 0");
         const int nnzA = hr[1];
+        plan_levels();
         allocate(nnzA);
-        const int kmax = std::max(1, o.n_eig) + 1;
-        sweep_tmp = A.alloc<T>((size_t)n * std::max(r, kmax));
+        if (nch > 1) reorder_input(rp, ci, val, nnzA);
         build_b0(rp, ci, val, nnzA);
         const bool prof = o.profile != 0;
-        // initial test vectors
-        LAUNCH(k_tv_init<T>, nblk((long long)n * r), BAMG_BLK, s, (long long)n * r, o.seed, L[0].U);
+        {
+            long long tot = (long long)n * r;
+            LAUNCH(k_tv_init<T>, nblk(tot), BAMG_BLK, s, tot, r, FastDiv((uint32_t)r), (const ChainGeo*)L[0].dgeo,
+                   L[0].nch, o.seed, L[0].U);
+        }
+        const int depth = (int)L.size();
         // down-leg: relax, fit, Galerkin, inject
-        const int nl = (int)L.size();
-        for (int l = 0; l + 1 < nl; ++l) {
+        for (int l = 0; l + 1 < depth; ++l) {
             sweeps(l, L[l].U, r, o.nu_setup, prof && l == 0);
-            build_level(l, r, 0, L[l].U, nullptr, L[l + 1].U, prof && l == 0);
+            build_level(l, 0, true, prof && l == 0);
         }
         if (o.stop_after == 1) { finish_setup(t0); return; }
         coarsest_inverse();
@@ -706,7 +848,7 @@ struct Engine : bamg_ctx {
         upleg();
         if (o.stop_after == 3) { finish_setup(t0); return; }
         // recompute every P, B, T from U u V
-        for (int l = 0; l + 1 < nl; ++l) build_level(l, r, nv, L[l].U, L[l].V, nullptr, prof && l == 0);
+        for (int l = 0; l + 1 < depth; ++l) build_level(l, 1, false, prof && l == 0);
         coarsest_inverse();
         finish_setup(t0);
     }
@@ -715,14 +857,9 @@ struct Engine : bamg_ctx {
         sync();
         st.t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         st.n_levels = (int)L.size();
-        st.n_v = nv;
+        st.n_v = nvmax;
         long long tot = 0;
-        for (auto& lv : L) {
-            int z;
-            HIPCHK(hipMemcpyAsync(&z, lv.B.rp + lv.n, sizeof(int), hipMemcpyDeviceToHost, s));
-            sync();
-            tot += z;
-        }
+        for (auto& lv : L) tot += get1(lv.B.rp + lv.rows);
         st.op_complexity = nnz0 > 0 ? (double)tot / nnz0 : 0.0;
         auto acc = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, double& ms, int& cnt) {
             ms = 0; cnt = 0;
@@ -738,164 +875,273 @@ struct Engine : bamg_ctx {
         acc(ev_gal, st.galerkin_ms, st.galerkin_launches);
         acc(ev_ls, st.lsfit_ms, st.lsfit_launches);
         // algorithmic bytes of one level-0 launch
-        const long long n0 = L[0].n;
+        const long long n0 = L[0].cont_rows;
         const int vb = sizeof(T);
         st.sweep_bytes = (long long)(n0 + 1) * 4 + (long long)nnz0 * (4 + vb) + n0 * vb + 2LL * n0 * r * vb;
         if (L.size() > 1) {
-            long long nc = L[1].n;
-            // numeric Galerkin of B: Q (9 per coarse row), B, P read; C written
+            long long nc = L[1].rows;
             st.galerkin_bytes = nc * 9 * (4 + vb) + (long long)(n0 + 1) * 4 + (long long)nnz0 * (4 + vb) +
                                 n0 * 4 * (4 + vb) + (nc + 1) * 4 + nc * 9 * (4 + vb);
-            st.lsfit_bytes = n0 * (long long)(r + nv) * vb + n0 * 4 * (4 + vb);
+            st.lsfit_bytes = n0 * (long long)(r + nvmax) * vb + n0 * 4 * (4 + vb);
         }
     }
 
     // -------------------------------------------------------------- cycle
-    // e_l = C f_l on level l (vectors in the level's cycle buffers, type T);
-    // result left in lv.e.
+    // e_l = C f_l on level l, result in lv.e (fixed buffers, so that the
+    // cycle can be replayed from a graph).  Continuing chains smooth and
+    // recurse; chains whose coarsest level is l take the minimal-norm solve.
     void vcycle(int l) {
         auto& lv = L[l];
-        if (l == (int)L.size() - 1) {
-            if (MIXED) {
-                LAUNCH(k_gemv_f32, ceil_div(nL, 4), BAMG_BLK, s, nL, nL, nL, (const float*)Wf, (const float*)lv.f,
-                       (float*)lv.e);
-            } else {
-                LAUNCH(k_gemv, ceil_div(nL, 4), BAMG_BLK, s, nL, nL, nL, (const double*)W, (const double*)lv.f,
-                       (double*)lv.e);
-            }
-            return;
+        if (lv.nch > lv.ncont) {
+            const int c0 = lv.ncont, c1 = lv.nch;
+            int maxn = 0;
+            for (int c = c0; c < c1; ++c) maxn = std::max(maxn, cdh[c].n);
+            const dim3 gw(ceil_div(maxn, 4), c1 - c0);
+            if (MIXED)
+                hipLaunchKernelGGL(k_cz_gemv_f32, gw, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)(cd + c0),
+                                   (const float*)Wfp, (const float*)lv.f, (float*)lv.e);
+            else
+                hipLaunchKernelGGL(k_cz_gemv_rows, gw, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)(cd + c0),
+                                   (const double*)Wp, (const double*)lv.f, (double*)lv.e);
+            HIPCHK(hipGetLastError());
         }
+        if (lv.ncont == 0) return;
         auto& c = L[l + 1];
+        const int rows = lv.cont_rows;
         FastDiv d1(1u);
-        T* cur = lv.e;
-        T* oth = lv.e2;
-        int nb = nblk(lv.n);
+        T* cur = lv.zero_into_e2 ? lv.e2 : lv.e;
+        T* oth = lv.zero_into_e2 ? lv.e : lv.e2;
+        const int nb = nblk(rows);
         if (o.nu_pre > 0) {
-            LAUNCH((k_jacobi_zero<T, T>), nb, BAMG_BLK, s, lv.n, (const T*)lv.dinv, (const T*)lv.f, cur);
+            LAUNCH((k_jacobi_zero<T, T>), nb, BAMG_BLK, s, rows, (const T*)lv.dinv, (const T*)lv.f, cur);
             for (int k = 1; k < o.nu_pre; ++k) {
-                LAUNCH((k_sweep<T, T>), nb, BAMG_BLK, s, lv.n, 1, d1, lv.B.rp, lv.B.ci, (const T*)lv.B.v,
+                LAUNCH((k_sweep<T, T>), nb, BAMG_BLK, s, rows, 1, d1, lv.B.rp, lv.B.ci, (const T*)lv.B.v,
                        (const T*)lv.dinv, (const T*)cur, (const T*)lv.f, oth);
                 std::swap(cur, oth);
             }
         } else {
-            zero(cur, sizeof(T) * lv.n);
+            LAUNCH((k_fill_t<T>), nb, BAMG_BLK, s, rows, cur);
         }
-        LAUNCH((k_residual<T, T>), nb, BAMG_BLK, s, lv.n, lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const T*)cur,
+        LAUNCH((k_residual<T, T>), nb, BAMG_BLK, s, rows, lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const T*)cur,
                (const T*)lv.f, lv.r);
-        LAUNCH((k_restrict<T, T>), nblk(c.n), BAMG_BLK, s, c.n, lv.qc, (const T*)lv.qv, (const T*)lv.r, c.f);
+        LAUNCH((k_restrict<T, T>), nblk(c.rows), BAMG_BLK, s, c.rows, lv.qc, (const T*)lv.qv, (const T*)lv.r, c.f);
         vcycle(l + 1);
-        LAUNCH((k_prolong_add<T, T>), nb, BAMG_BLK, s, lv.n, lv.pc, (const T*)lv.pv, (const T*)c.e, cur);
+        LAUNCH((k_prolong_add<T, T>), nb, BAMG_BLK, s, rows, lv.pc, (const T*)lv.pv, (const T*)c.e, cur);
         for (int k = 0; k < o.nu_post; ++k) {
-            LAUNCH((k_sweep<T, T>), nb, BAMG_BLK, s, lv.n, 1, d1, lv.B.rp, lv.B.ci, (const T*)lv.B.v,
+            LAUNCH((k_sweep<T, T>), nb, BAMG_BLK, s, rows, 1, d1, lv.B.rp, lv.B.ci, (const T*)lv.B.v,
                    (const T*)lv.dinv, (const T*)cur, (const T*)lv.f, oth);
             std::swap(cur, oth);
         }
-        if (cur != lv.e) std::swap(lv.e, lv.e2);   // keep the result in lv.e
+        if (cur != lv.e) fail(BAMG_EDEVICE, "cycle buffer parity");
     }
 
-    // z = C v for FP64 level-0 vectors.
-    void precondition(const double* v, double* z);
+    // One cycle from L[0].f into L[0].e, replayed from a captured graph.
+    void run_cycle() {
+        if (!gexec) {
+            // Record the launches of one cycle on a private stream (nothing
+            // runs during capture), then replay the graph on the handle's
+            // stream, which may be the legacy default stream.
+            if (!cap_s) HIPCHK(hipStreamCreateWithFlags(&cap_s, hipStreamNonBlocking));
+            hipStream_t user = s;
+            s = cap_s;
+            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            try {
+                vcycle(0);
+            } catch (...) {
+                hipGraph_t gtmp = nullptr;
+                (void)hipStreamEndCapture(s, &gtmp);
+                if (gtmp) (void)hipGraphDestroy(gtmp);
+                s = user;
+                throw;
+            }
+            const hipError_t ec = hipStreamEndCapture(s, &graph);
+            s = user;
+            HIPCHK(ec);
+            HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+        }
+        HIPCHK(hipGraphLaunch(gexec, s));
+    }
 
+    // z = C v for FP64 finest-level vectors.
+    void precondition(const double* v, double* z) {
+        auto& l0 = L[0];
+        if (MIXED) LAUNCH(k_d2f, nblk(n), BAMG_BLK, s, (int)n, v, (float*)l0.f);
+        else LAUNCH(k_copy, nblk(n), BAMG_BLK, s, (long long)n, v, (double*)l0.f);
+        run_cycle();
+        if (MIXED) LAUNCH(k_f2d, nblk(n), BAMG_BLK, s, (int)n, (const float*)l0.e, z);
+        else LAUNCH(k_copy, nblk(n), BAMG_BLK, s, (long long)n, (const double*)l0.e, z);
+    }
+
+    // Caller's chain order in and out (the handle's rows are depth-sorted).
     void vcycle_apply(const double* f, double* e) override {
-        precondition(f, e);
+        if (!reordered) {
+            precondition(f, e);
+        } else {
+            if (!vin) { vin = A.alloc<double>(n); vout = A.alloc<double>(n); }
+            const dim3 gp(nblk(n), nch);
+            hipLaunchKernelGGL(k_seg_permute, gp, dim3(BAMG_BLK), 0, s, (const int*)perm_src, (const int*)perm_dst,
+                               (const int*)perm_len, f, vin);
+            HIPCHK(hipGetLastError());
+            precondition(vin, vout);
+            hipLaunchKernelGGL(k_seg_permute, gp, dim3(BAMG_BLK), 0, s, (const int*)perm_dst, (const int*)perm_src,
+                               (const int*)perm_len, (const double*)vout, e);
+            HIPCHK(hipGetLastError());
+        }
         sync();
     }
 
     // -------------------------------------------------------------- solve
-    int solve(double* x, double tol, int max_cycles, uint32_t flags, bamg_solve_info* info) override {
+    // Flexible GMRES(m) on B x = 0 for every chain at once: vectors are the
+    // concatenated finest rows; dot products, Hessenberg matrices and the
+    // convergence decisions are per chain.  A chain whose inner iteration has
+    // stopped is masked until the restart.
+    int solve(double* x, double tol, int max_cycles, uint32_t flags, int32_t* status, double* resid,
+              bamg_solve_info* info) override {
         auto t0 = std::chrono::steady_clock::now();
         const int m = std::max(1, o.gmres_m);
         const int N = (int)n;
-        if (!Vk) {
+        const int ld = m + 1;
+        const int HSg = (m + 1) * m, GS = m + 2;
+        if (m_alloc != m) {
             Vk = A.alloc<double>((size_t)(m + 1) * N);
             Zk = A.alloc<double>((size_t)m * N);
             wk = A.alloc<double>(N);
             rvec = A.alloc<double>(N);
-            Hg = A.alloc<double>((size_t)(m + 1) * m);
-            cs = A.alloc<double>(m + 1);
-            sn = A.alloc<double>(m + 1);
-            g = A.alloc<double>(m + 2);
-            ysol = A.alloc<double>(m + 1);
-            hbuf = A.alloc<double>(m + 2);
+            Hg = A.alloc<double>((size_t)nch * HSg);
+            cs = A.alloc<double>((size_t)nch * GS);
+            sn = A.alloc<double>((size_t)nch * GS);
+            g = A.alloc<double>((size_t)nch * GS);
+            ysol = A.alloc<double>((size_t)nch * GS);
+            hbuf = A.alloc<double>((size_t)nch * GS);
+            est = A.alloc<double>(nch);
+            act = A.alloc<int>(nch);
+            kd = A.alloc<int>(nch);
+            if (reordered) xperm = A.alloc<double>(N);
+            m_alloc = m;
         }
+        double* xi = reordered ? xperm : x;
         bamg_solve_info inf{};
-        if (!(flags & BAMG_USE_GUESS)) HIPCHK(hipMemcpyAsync(x, x0, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+        if (!(flags & BAMG_USE_GUESS)) {
+            HIPCHK(hipMemcpyAsync(xi, x0, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+        } else if (reordered) {
+            hipLaunchKernelGGL(k_seg_permute, dim3(nblk(N), nch), dim3(BAMG_BLK), 0, s, (const int*)perm_src,
+                               (const int*)perm_dst, (const int*)perm_len, (const double*)x, xi);
+            HIPCHK(hipGetLastError());
+        }
+        const ChainGeo* g0 = L[0].dgeo;
         auto normalise = [&]() {
-            reduce<RED_SUM>(N, x, nullptr, sc + 20);
-            LAUNCH(k_scale, nblk(N), BAMG_BLK, s, N, (const double*)x, (const double*)nullptr, (const double*)(sc + 20),
-                   0, x);
+            seg_reduce<RED_SUM>(xi, nullptr, sc);
+            LAUNCH(k_seg_scale, nblk(N), BAMG_BLK, s, N, g0, nch, (const int*)nullptr, (const double*)xi,
+                   (const double*)nullptr, (const double*)sc, SCS, 0, xi);
         };
         normalise();
         const int nb = nblk(N);
+        std::vector<int> conv(nch, 0), hact(nch), hkd(nch);
+        std::vector<double> rel(nch, 0.0);
         for (;;) {
-            // r = -B x; relative 1-norm residual
-            LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)x, -1.0, rvec);
-            reduce<RED_ABS>(N, rvec, nullptr, sc + 21);
-            reduce<RED_ABS>(N, x, nullptr, sc + 22);
-            reduce<RED_DOT>(N, rvec, rvec, sc + 23);
-            double h3[3];
-            HIPCHK(hipMemcpyAsync(h3, sc + 21, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
-            sync();
-            double rel = h3[0] / h3[1];
-            inf.residual_l1 = rel;
-            if (inf.history_len < 256) inf.history[inf.history_len++] = rel;
-            if (rel <= tol) { inf.converged = 1; break; }
-            if (inf.cycles >= max_cycles || !(rel == rel)) break;
-            double beta = std::sqrt(h3[2]);
-            double inner_tol = 0.5 * tol * h3[1] * beta / h3[0];
-            zero(Hg, sizeof(double) * (m + 1) * m);
-            LAUNCH(k_gmres_init, 1, 64, s, m, (const double*)(sc + 23), g);
-            LAUNCH(k_scale, nb, BAMG_BLK, s, N, (const double*)rvec, (const double*)nullptr, (const double*)(sc + 23),
-                   1, Vk);
-            int kdone = 0;
+            // r = -B x; per-chain relative 1-norm residual
+            LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)xi, -1.0, rvec);
+            seg_reduce<RED_ABS>(rvec, nullptr, sc + 1);
+            seg_reduce<RED_ABS>(xi, nullptr, sc + 2);
+            seg_reduce<RED_DOT>(rvec, rvec, sc + 3);
+            std::vector<double> h = getn(sc, (size_t)nch * SCS);
+            bool all = true, nan = false;
+            double worst = 0;
+            for (int c = 0; c < nch; ++c) {
+                rel[c] = h[(size_t)c * SCS + 1] / h[(size_t)c * SCS + 2];
+                conv[c] = rel[c] <= tol;
+                all &= (bool)conv[c];
+                nan |= !(rel[c] == rel[c]);
+                worst = std::max(worst, rel[c]);
+            }
+            inf.residual_l1 = worst;
+            if (inf.history_len < 256) inf.history[inf.history_len++] = worst;
+            if (all || inf.cycles >= max_cycles || nan) break;
+            // inner iteration for the unconverged chains
+            std::vector<double> itol(nch);
+            for (int c = 0; c < nch; ++c) {
+                double r1 = h[(size_t)c * SCS + 1], x1 = h[(size_t)c * SCS + 2], b2 = h[(size_t)c * SCS + 3];
+                itol[c] = 0.5 * tol * x1 * std::sqrt(b2) / r1;
+                hact[c] = conv[c] ? 0 : 1;
+                hkd[c] = 0;
+            }
+            HIPCHK(hipMemcpyAsync(act, hact.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
+            zero(Hg, sizeof(double) * nch * HSg);
+            LAUNCH(k_seg_gmres_init, nch, 64, s, nch, m, (const double*)(sc + 3), SCS, g, GS);
+            LAUNCH(k_seg_scale, nb, BAMG_BLK, s, N, g0, nch, (const int*)nullptr, (const double*)rvec,
+                   (const double*)nullptr, (const double*)(sc + 3), SCS, 1, Vk);
             for (int j = 0; j < m && inf.cycles < max_cycles; ++j) {
                 double* vj = Vk + (size_t)j * N;
                 double* zj = Zk + (size_t)j * N;
                 precondition(vj, zj);
                 ++inf.cycles;
                 LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)zj, 1.0, wk);
-                double* hcol = Hg + (size_t)j * (m + 1);
                 for (int pass = 0; pass < 2; ++pass) {
-                    LAUNCH(k_mdot_partial, MDOT_BLOCKS, BAMG_BLK, s, N, j + 1, (const double*)Vk, (const double*)wk,
-                           part);
-                    LAUNCH(k_mdot_final, j + 1, BAMG_BLK, s, MDOT_BLOCKS * (BAMG_BLK / BAMG_WAVE), j + 1,
-                           (const double*)part, hbuf, hcol);
-                    LAUNCH(k_vupdate, nb, BAMG_BLK, s, N, j + 1, (const double*)Vk, (const double*)hbuf, wk);
+                    hipLaunchKernelGGL(k_seg_mdot_partial, dim3(MDOT_PARTS, nch), dim3(BAMG_BLK), 0, s, g0, N, j + 1,
+                                       (const int*)act, (const double*)Vk, (const double*)wk, part);
+                    hipLaunchKernelGGL(k_seg_mdot_final, dim3(j + 1, nch), dim3(BAMG_BLK), 0, s,
+                                       MDOT_PARTS * (BAMG_BLK / BAMG_WAVE), j + 1, (const int*)act, (const double*)part,
+                                       hbuf, GS, Hg + (size_t)j * ld, HSg);
+                    HIPCHK(hipGetLastError());
+                    LAUNCH(k_seg_vupdate, nb, BAMG_BLK, s, N, g0, nch, j + 1, (const int*)act, (const double*)Vk,
+                           (const double*)hbuf, GS, wk);
                 }
-                reduce<RED_DOT>(N, wk, wk, sc + 24);
-                LAUNCH(k_scale, nb, BAMG_BLK, s, N, (const double*)wk, (const double*)nullptr, (const double*)(sc + 24),
-                       1, Vk + (size_t)(j + 1) * N);
-                LAUNCH(k_givens, 1, 64, s, j, m + 1, Hg, (const double*)(sc + 24), cs, sn, g, sc + 26);
-                double h3b[3];
-                HIPCHK(hipMemcpyAsync(h3b, sc + 24, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
-                sync();
-                double hn = std::sqrt(h3b[0]), est = h3b[2];
-                kdone = j + 1;
-                if (est <= inner_tol || hn == 0.0) break;
+                seg_reduce<RED_DOT>(wk, wk, sc + 4);
+                LAUNCH(k_seg_scale, nb, BAMG_BLK, s, N, g0, nch, (const int*)act, (const double*)wk,
+                       (const double*)nullptr, (const double*)(sc + 4), SCS, 1, Vk + (size_t)(j + 1) * N);
+                LAUNCH(k_seg_givens, ceil_div(nch, 64), 64, s, nch, j, ld, (const int*)act, Hg, HSg,
+                       (const double*)(sc + 4), SCS, cs, sn, g, GS, est);
+                std::vector<double> e = getn(est, nch);
+                std::vector<double> hn = getn(sc, (size_t)nch * SCS);
+                bool any = false;
+                for (int c = 0; c < nch; ++c) {
+                    if (!hact[c]) continue;
+                    hkd[c] = j + 1;
+                    if (e[c] <= itol[c] || hn[(size_t)c * SCS + 4] == 0.0) hact[c] = 0;
+                    any |= (bool)hact[c];
+                }
+                HIPCHK(hipMemcpyAsync(act, hact.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
+                if (!any) break;
             }
-            if (kdone > 0) {
-                LAUNCH(k_gmres_y, 1, 64, s, kdone, m + 1, (const double*)Hg, (const double*)g, ysol);
-                LAUNCH(k_xupdate, nb, BAMG_BLK, s, N, kdone, (const double*)Zk, (const double*)ysol, x);
-            }
+            HIPCHK(hipMemcpyAsync(kd, hkd.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
+            LAUNCH(k_seg_gmres_y, ceil_div(nch, 64), 64, s, nch, ld, (const int*)kd, (const double*)Hg, HSg,
+                   (const double*)g, GS, ysol);
+            LAUNCH(k_seg_xupdate, nb, BAMG_BLK, s, N, g0, nch, (const int*)kd, (const double*)Zk, (const double*)ysol,
+                   GS, xi);
             normalise();
             ++inf.restarts;
         }
-        // x >= 0, sum 1
-        reduce<RED_NEGSUM>(N, x, nullptr, sc + 27);
-        LAUNCH(k_clamp, nb, BAMG_BLK, s, N, x);
+        // x >= 0, sum 1 per chain
+        seg_reduce<RED_NEGSUM>(xi, nullptr, sc + 5);
+        LAUNCH(k_clamp, nb, BAMG_BLK, s, N, xi);
         normalise();
-        LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)x, -1.0, rvec);
-        reduce<RED_ABS>(N, rvec, nullptr, sc + 21);
-        reduce<RED_ABS>(N, x, nullptr, sc + 22);
-        double h4[7];
-        HIPCHK(hipMemcpyAsync(h4, sc + 21, sizeof(double) * 7, hipMemcpyDeviceToHost, s));
-        sync();
-        inf.residual_l1 = h4[0] / h4[1];
-        inf.clamped_mass = h4[6];
-        inf.converged = inf.residual_l1 <= tol;
+        LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)xi, -1.0, rvec);
+        seg_reduce<RED_ABS>(rvec, nullptr, sc + 1);
+        seg_reduce<RED_ABS>(xi, nullptr, sc + 2);
+        if (reordered) {
+            // back to the caller's order (source and destination swapped)
+            hipLaunchKernelGGL(k_seg_permute, dim3(nblk(N), nch), dim3(BAMG_BLK), 0, s, (const int*)perm_dst,
+                               (const int*)perm_src, (const int*)perm_len, (const double*)xi, x);
+            HIPCHK(hipGetLastError());
+        }
+        std::vector<double> h = getn(sc, (size_t)nch * SCS);
+        double worst = 0, cm = 0;
+        bool all = true;
+        for (int c = 0; c < nch; ++c) {
+            double rc = h[(size_t)c * SCS + 1] / h[(size_t)c * SCS + 2];
+            worst = std::max(worst, rc);
+            cm = std::max(cm, h[(size_t)c * SCS + 5]);
+            all &= rc <= tol;
+            const int u = chains[c].uidx;
+            if (status) status[u] = rc <= tol ? 1 : 0;
+            if (resid) resid[u] = rc;
+        }
+        inf.residual_l1 = worst;
+        inf.clamped_mass = cm;
+        inf.converged = all;
         st.t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         if (info) *info = inf;
-        return inf.converged ? BAMG_OK : BAMG_ENOCONV;
+        return all ? BAMG_OK : BAMG_ENOCONV;
     }
 
     // -------------------------------------------------------------- inspection
@@ -903,70 +1149,67 @@ struct Engine : bamg_ctx {
         if (l < 0 || l >= (int)L.size()) fail(BAMG_EINVAL, "level %d out of range", l);
         auto& lv = L[l];
         memset(out, 0, sizeof *out);
-        out->n = lv.n;
-        out->nx = lv.g.nx; out->ny = lv.g.ny; out->periodic = lv.g.periodic;
-        int z = 0;
-        HIPCHK(hipMemcpyAsync(&z, lv.B.rp + lv.n, sizeof(int), hipMemcpyDeviceToHost, s));
-        sync();
-        out->nnz_b = z;
-        if (lv.Tm.rp) {
-            HIPCHK(hipMemcpyAsync(&z, lv.Tm.rp + lv.n, sizeof(int), hipMemcpyDeviceToHost, s));
-            sync();
-            out->nnz_t = z;
-        }
-        if (lv.pc) out->nnz_p = 4LL * lv.n;
+        out->n = lv.rows;
+        out->nx = lv.geo[0].nx; out->ny = lv.geo[0].ny; out->periodic = lv.geo[0].periodic;
+        out->nnz_b = get1(lv.B.rp + lv.rows);
+        if (lv.Tm.rp) out->nnz_t = get1(lv.Tm.rp + lv.rows);
+        if (lv.pc) out->nnz_p = 4LL * lv.cont_rows;
         out->r = r;
-        out->n_v = nv;
+        out->n_v = nvmax;
     }
 
     template <typename X>
     void copy_out(const X* src, size_t count, void* dst, size_t bytes) {
         if (bytes < count * sizeof(X)) fail(BAMG_EINVAL, "export buffer too small (%zu < %zu)", bytes, count * sizeof(X));
-        HIPCHK(hipMemcpyAsync(dst, src, count * sizeof(X), hipMemcpyDeviceToHost, s));
+        if (count) HIPCHK(hipMemcpyAsync(dst, src, count * sizeof(X), hipMemcpyDeviceToHost, s));
         sync();
     }
-    void copy_out_T(const T* src, size_t count, void* dst, size_t bytes) {
-        if (bytes < count * sizeof(double)) fail(BAMG_EINVAL, "export buffer too small");
-        if (!MIXED) { copy_out((const double*)src, count, dst, bytes); return; }
-        std::vector<T> h(count);
-        HIPCHK(hipMemcpyAsync(h.data(), src, count * sizeof(T), hipMemcpyDeviceToHost, s));
+    // T array (rows x ldv) -> host doubles (rows x cols)
+    void copy_out_T(const T* src, size_t rows, size_t ldv, size_t cols, void* dst, size_t bytes) {
+        if (bytes < rows * cols * sizeof(double)) fail(BAMG_EINVAL, "export buffer too small");
+        std::vector<T> h(rows * ldv);
+        if (!h.empty()) HIPCHK(hipMemcpyAsync(h.data(), src, h.size() * sizeof(T), hipMemcpyDeviceToHost, s));
         sync();
-        for (size_t i = 0; i < count; ++i) ((double*)dst)[i] = (double)h[i];
+        double* o2 = (double*)dst;
+        for (size_t i = 0; i < rows; ++i)
+            for (size_t k = 0; k < cols; ++k) o2[i * cols + k] = (double)h[i * ldv + k];
     }
 
     void export_item(int l, int what, void* dst, size_t bytes) override {
+        if (nch != 1) fail(BAMG_EINVAL, "export is available for single-chain handles");
         if (l < 0 || l >= (int)L.size()) fail(BAMG_EINVAL, "level %d out of range", l);
         auto& lv = L[l];
         sync();
-        int nnzb = 0, nnzt = 0;
-        HIPCHK(hipMemcpyAsync(&nnzb, lv.B.rp + lv.n, sizeof(int), hipMemcpyDeviceToHost, s));
-        if (lv.Tm.rp) HIPCHK(hipMemcpyAsync(&nnzt, lv.Tm.rp + lv.n, sizeof(int), hipMemcpyDeviceToHost, s));
-        sync();
+        const int rows = lv.rows;
+        const int nnzb = get1(lv.B.rp + rows);
+        const int nnzt = lv.Tm.rp ? get1(lv.Tm.rp + rows) : 0;
         const bool last = l == (int)L.size() - 1;
+        const int nL = cdh[0].n;
         switch (what) {
-            case BAMG_X_B_ROWPTR: copy_out(lv.B.rp, lv.n + 1, dst, bytes); break;
+            case BAMG_X_B_ROWPTR: copy_out(lv.B.rp, rows + 1, dst, bytes); break;
             case BAMG_X_B_COL: copy_out(lv.B.ci, nnzb, dst, bytes); break;
             case BAMG_X_B_VAL:
                 if (l == 0) copy_out((const double*)b0v, nnzb, dst, bytes);
-                else copy_out_T(lv.B.v, nnzb, dst, bytes);
+                else copy_out_T(lv.B.v, nnzb, 1, 1, dst, bytes);
                 break;
-            case BAMG_X_T_ROWPTR: if (!lv.Tm.rp) fail(BAMG_EINVAL, "T_0 = I is not stored"); copy_out(lv.Tm.rp, lv.n + 1, dst, bytes); break;
+            case BAMG_X_T_ROWPTR: if (!lv.Tm.rp) fail(BAMG_EINVAL, "T_0 = I is not stored"); copy_out(lv.Tm.rp, rows + 1, dst, bytes); break;
             case BAMG_X_T_COL: if (!lv.Tm.rp) fail(BAMG_EINVAL, "T_0 = I is not stored"); copy_out(lv.Tm.ci, nnzt, dst, bytes); break;
-            case BAMG_X_T_VAL: if (!lv.Tm.rp) fail(BAMG_EINVAL, "T_0 = I is not stored"); copy_out_T(lv.Tm.v, nnzt, dst, bytes); break;
-            case BAMG_X_P_COL: if (!lv.pc) fail(BAMG_EINVAL, "no P on the coarsest level"); copy_out(lv.pc, (size_t)lv.n * 4, dst, bytes); break;
-            case BAMG_X_P_VAL: if (!lv.pc) fail(BAMG_EINVAL, "no P on the coarsest level"); copy_out_T(lv.pv, (size_t)lv.n * 4, dst, bytes); break;
-            case BAMG_X_U: copy_out_T(lv.U, (size_t)lv.n * r, dst, bytes); break;
-            case BAMG_X_V: copy_out_T(lv.V, (size_t)lv.n * nv, dst, bytes); break;
-            case BAMG_X_LAMBDA: copy_out(lam, 2 * (size_t)nv, dst, bytes); break;
-            case BAMG_X_VKIND: copy_out(kind, nv, dst, bytes); break;
-            case BAMG_X_X0: if (l != 0) fail(BAMG_EINVAL, "x0 lives on level 0"); copy_out(x0, lv.n, dst, bytes); break;
-            case BAMG_X_W: if (!last) fail(BAMG_EINVAL, "W lives on the coarsest level"); copy_out(W, (size_t)nL * nL, dst, bytes); break;
-            case BAMG_X_Y: if (!last) fail(BAMG_EINVAL, "y lives on the coarsest level"); copy_out(y, nL, dst, bytes); break;
+            case BAMG_X_T_VAL: if (!lv.Tm.rp) fail(BAMG_EINVAL, "T_0 = I is not stored"); copy_out_T(lv.Tm.v, nnzt, 1, 1, dst, bytes); break;
+            case BAMG_X_P_COL: if (!lv.pc) fail(BAMG_EINVAL, "no P on the coarsest level"); copy_out(lv.pc, (size_t)rows * 4, dst, bytes); break;
+            case BAMG_X_P_VAL: if (!lv.pc) fail(BAMG_EINVAL, "no P on the coarsest level"); copy_out_T(lv.pv, (size_t)rows * 4, 1, 1, dst, bytes); break;
+            case BAMG_X_U: copy_out_T(lv.U, (size_t)rows * r, 1, 1, dst, bytes); break;
+            case BAMG_X_V: copy_out_T(lv.V, rows, VS, nvmax, dst, bytes); break;
+            case BAMG_X_LAMBDA: copy_out(lam, 2 * (size_t)nvmax, dst, bytes); break;
+            case BAMG_X_VKIND: copy_out(kind, nvmax, dst, bytes); break;
+            case BAMG_X_X0: if (l != 0) fail(BAMG_EINVAL, "x0 lives on level 0"); copy_out(x0, rows, dst, bytes); break;
+            case BAMG_X_W: if (!last) fail(BAMG_EINVAL, "W lives on the coarsest level"); copy_out(Wp, (size_t)nL * nL, dst, bytes); break;
+            case BAMG_X_Y: if (!last) fail(BAMG_EINVAL, "y lives on the coarsest level"); copy_out(ypool, nL, dst, bytes); break;
             case BAMG_X_U0: {
                 if (l != 0) fail(BAMG_EINVAL, "U0 lives on level 0");
-                T* tmp = sweep_tmp;
-                LAUNCH(k_tv_init<T>, nblk((long long)n * r), BAMG_BLK, s, (long long)n * r, o.seed, tmp);
-                copy_out_T(tmp, (size_t)n * r, dst, bytes);
+                long long tot = (long long)n * r;
+                LAUNCH(k_tv_init<T>, nblk(tot), BAMG_BLK, s, tot, r, FastDiv((uint32_t)r), (const ChainGeo*)L[0].dgeo,
+                       L[0].nch, o.seed, sweep_tmp);
+                copy_out_T(sweep_tmp, (size_t)n * r, 1, 1, dst, bytes);
                 break;
             }
             default: fail(BAMG_EINVAL, "unknown export item %d", what);
@@ -974,25 +1217,6 @@ struct Engine : bamg_ctx {
     }
 };
 
-template <>
-void Engine<double>::precondition(const double* v, double* z) {
-    auto& l0 = L[0];
-    HIPCHK(hipMemcpyAsync(l0.f, v, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    vcycle(0);
-    HIPCHK(hipMemcpyAsync(z, l0.e, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-}
-template <>
-void Engine<float>::precondition(const double* v, double* z) {
-    auto& l0 = L[0];
-    LAUNCH(k_d2f, nblk(n), BAMG_BLK, s, (int)n, v, l0.f);
-    vcycle(0);
-    LAUNCH(k_f2d, nblk(n), BAMG_BLK, s, (int)n, (const float*)l0.e, z);
-}
-
-}  // namespace
-
-// ------------------------------------------------------------------ C ABI
-namespace {
 int run_guarded(const std::function<void()>& fn) {
     try {
         fn();
@@ -1009,8 +1233,69 @@ int run_guarded(const std::function<void()>& fn) {
         return BAMG_EDEVICE;
     }
 }
+
+void check_options(const bamg_options& o) {
+    if (o.nu_setup < 0 || o.nu_pre < 0 || o.nu_post < 0 || !(o.omega > 0) || o.caliber < 1 || o.n_eig < 1 ||
+        o.n_eig > 8 || o.gmres_m < 1 || o.gmres_m > 200 || o.arnoldi_m < 1 || o.levels < 0 || o.coarse_max < 1)
+        fail(BAMG_EINVAL, "invalid options");
+    if (o.interp != BAMG_INTERP_LS) fail(BAMG_EUNSUPPORTED, "interpolation mode %d not available", o.interp);
+    if (o.precision != BAMG_FP64 && o.precision != BAMG_MIXED) fail(BAMG_EINVAL, "unknown precision %d", o.precision);
+}
+
+bamg_ctx* make_ctx(const bamg_options& o) {
+    if (o.precision == BAMG_MIXED) return new Engine<float>();
+    return new Engine<double>();
+}
+
+int setup_common(int32_t nchains, const int64_t* off, const int32_t* row_ptr, const int32_t* col_idx,
+                 const double* val, const bamg_grid* grids, int32_t r, const bamg_options* opt, void* stream,
+                 bamg_handle* out) {
+    bamg_ctx* ctx = nullptr;
+    int rc = run_guarded([&] {
+        if (!out) fail(BAMG_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (!row_ptr || !col_idx || !val || !grids || !off) fail(BAMG_EINVAL, "NULL argument");
+        if (nchains < 1 || nchains > 4096) fail(BAMG_EINVAL, "nchains = %d out of range", nchains);
+        if (r < 1 || r > 32) fail(BAMG_EINVAL, "r = %d out of range [1, 32]", r);
+        if (off[0] != 0) fail(BAMG_EINVAL, "chain_row_off[0] must be 0");
+        const long long n = off[nchains];
+        if (n < 1 || n > (1LL << 30)) fail(BAMG_EINVAL, "n = %lld out of range", n);
+        bamg_options o;
+        if (opt) o = *opt; else bamg_options_default(&o);
+        check_options(o);
+        std::vector<ChainH> ch(nchains);
+        for (int c = 0; c < nchains; ++c) {
+            const bamg_grid& gr = grids[c];
+            const long long nc = off[c + 1] - off[c];
+            if (nc < 1) fail(BAMG_EINVAL, "chain %d is empty", c);
+            if (gr.nx < 1 || gr.ny < 1 || (long long)gr.nx * gr.ny != nc)
+                fail(BAMG_EINVAL, "grid %dx%d of chain %d does not match its %lld states", gr.nx, gr.ny, c, nc);
+            if (gr.periodic && (gr.nx < 3 || gr.ny < 3)) fail(BAMG_EUNSUPPORTED, "periodic sides must be >= 3");
+            ch[c].uidx = c;
+            ch[c].uoff = off[c];
+            ch[c].n = nc;
+            ch[c].grid = GridH{gr.nx, gr.ny, gr.periodic ? 1 : 0};
+            ch[c].plan = level_plan(ch[c].grid, o.levels, o.coarse_max);
+        }
+        std::stable_sort(ch.begin(), ch.end(),
+                         [](const ChainH& a, const ChainH& b) { return a.plan.size() > b.plan.size(); });
+        ctx = make_ctx(o);
+        ctx->s = (hipStream_t)stream;
+        ctx->o = o;
+        ctx->r = r;
+        ctx->n = n;
+        ctx->nch = nchains;
+        ctx->chains = ch;
+        ctx->setup(row_ptr, col_idx, val);
+        *out = ctx;
+    });
+    if (rc != BAMG_OK) delete ctx;
+    return rc;
+}
+
 }  // namespace
 
+// ------------------------------------------------------------------ C ABI
 extern "C" {
 
 void bamg_options_default(bamg_options* opt) {
@@ -1035,35 +1320,19 @@ const char* bamg_last_error(void) { return g_last_error.c_str(); }
 
 int bamg_setup(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const double* val, bamg_grid grid,
                int32_t r, const bamg_options* opt, void* stream, bamg_handle* out) {
-    bamg_ctx* ctx = nullptr;
-    int rc = run_guarded([&] {
-        if (!out) fail(BAMG_EINVAL, "out is NULL");
-        *out = nullptr;
-        if (!row_ptr || !col_idx || !val) fail(BAMG_EINVAL, "CSR pointer is NULL");
-        if (n < 1 || n > (1LL << 30)) fail(BAMG_EINVAL, "n = %lld out of range", (long long)n);
-        if (r < 1 || r > 32) fail(BAMG_EINVAL, "r = %d out of range [1, 32]", r);
-        if (grid.nx < 1 || grid.ny < 1 || (long long)grid.nx * grid.ny != n)
-            fail(BAMG_EINVAL, "grid %dx%d does not match n = %lld", grid.nx, grid.ny, (long long)n);
-        if (grid.periodic && (grid.nx < 3 || grid.ny < 3)) fail(BAMG_EUNSUPPORTED, "periodic sides must be >= 3");
-        bamg_options o;
-        if (opt) o = *opt; else bamg_options_default(&o);
-        if (o.nu_setup < 0 || o.nu_pre < 0 || o.nu_post < 0 || !(o.omega > 0) || o.caliber < 1 || o.n_eig < 1 ||
-            o.n_eig > 8 || o.gmres_m < 1 || o.gmres_m > 200 || o.arnoldi_m < 1 || o.levels < 0 || o.coarse_max < 1)
-            fail(BAMG_EINVAL, "invalid options");
-        if (o.interp != BAMG_INTERP_LS) fail(BAMG_EUNSUPPORTED, "interpolation mode %d not available", o.interp);
-        if (o.precision == BAMG_FP64) ctx = new Engine<double>();
-        else if (o.precision == BAMG_MIXED) ctx = new Engine<float>();
-        else fail(BAMG_EINVAL, "unknown precision %d", o.precision);
-        ctx->s = (hipStream_t)stream;
-        ctx->o = o;
-        ctx->r = r;
-        ctx->n = n;
-        ctx->grid = GridH{grid.nx, grid.ny, grid.periodic ? 1 : 0};
-        ctx->setup(row_ptr, col_idx, val);
-        *out = ctx;
-    });
-    if (rc != BAMG_OK) delete ctx;
-    return rc;
+    int64_t off[2] = {0, n};
+    if (n < 1) {
+        if (out) *out = nullptr;
+        g_last_error = "n < 1";
+        return BAMG_EINVAL;
+    }
+    return setup_common(1, off, row_ptr, col_idx, val, &grid, r, opt, stream, out);
+}
+
+int bamg_setup_batched(int32_t nchains, const int64_t* chain_row_off, const int32_t* row_ptr, const int32_t* col_idx,
+                       const double* val, const bamg_grid* grids, int32_t r, const bamg_options* opt, void* stream,
+                       bamg_handle* out) {
+    return setup_common(nchains, chain_row_off, row_ptr, col_idx, val, grids, r, opt, stream, out);
 }
 
 int bamg_solve(bamg_handle h, double* x, double tol, int32_t max_cycles, uint32_t flags, bamg_solve_info* info) {
@@ -1071,11 +1340,23 @@ int bamg_solve(bamg_handle h, double* x, double tol, int32_t max_cycles, uint32_
     int rc = run_guarded([&] {
         if (!h || !x) fail(BAMG_EINVAL, "NULL handle or x");
         if (!(tol > 0) || max_cycles < 0) fail(BAMG_EINVAL, "invalid tol or max_cycles");
-        code = h->solve(x, tol, max_cycles, flags, info);
-        if (code == BAMG_ENOCONV) g_last_error = "tolerance not reached";
+        code = h->solve(x, tol, max_cycles, flags, nullptr, nullptr, info);
     });
     if (rc != BAMG_OK) return rc;
     if (code == BAMG_ENOCONV) g_last_error = "tolerance not reached within max_cycles";
+    return code;
+}
+
+int bamg_solve_batched(bamg_handle h, double* x, double tol, int32_t max_cycles, uint32_t flags, int32_t* chain_status,
+                       double* chain_residual, bamg_solve_info* info) {
+    int code = BAMG_OK;
+    int rc = run_guarded([&] {
+        if (!h || !x) fail(BAMG_EINVAL, "NULL handle or x");
+        if (!(tol > 0) || max_cycles < 0) fail(BAMG_EINVAL, "invalid tol or max_cycles");
+        code = h->solve(x, tol, max_cycles, flags, chain_status, chain_residual, info);
+    });
+    if (rc != BAMG_OK) return rc;
+    if (code == BAMG_ENOCONV) g_last_error = "tolerance not reached within max_cycles for some chain";
     return code;
 }
 
@@ -1128,11 +1409,11 @@ int bamg_relax(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const 
         HIPCHK(hipMemcpyAsync(&hr[1], row_ptr + n, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (hr[0] != 0 || hr[1] < 0) fail(BAMG_EINVAL, "row_ptr[0] must be 0");
-        int N = (int)n;
-        // validate as a 1 x n grid would reject wide stencils; relaxation itself
-        // needs no grid, so use a grid of one row of n states (every offset is
-        // then a b-offset) with the 3x3-box test disabled through n x 1.
-        GridDev gd{N, 1, 0, FastDiv(1u)};
+        const int N = (int)n;
+        // relaxation needs no grid: one chain on an N x 1 grid, box test ignored
+        std::vector<ChainGeo> gv(1);
+        gv[0].off = 0; gv[0].n = N; gv[0].nx = N; gv[0].ny = 1; gv[0].periodic = 0; gv[0].dy = FastDiv(1u);
+        ChainGeo* dg = A.upload(gv);
         double* colsum = A.alloc<double>(N);
         int* cnt = A.alloc<int>(N);
         int* brp = A.alloc<int>(N + 1);
@@ -1141,7 +1422,8 @@ int bamg_relax(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const 
         int* total = A.alloc<int>(2);
         HIPCHK(hipMemsetAsync(colsum, 0, sizeof(double) * N, s));
         HIPCHK(hipMemsetAsync(err, 0, sizeof(int) * 4, s));
-        LAUNCH(k_check_a, nblk(N), BAMG_BLK, s, N, row_ptr, col_idx, val, gd, hr[1], colsum, cnt, err);
+        LAUNCH(k_check_a, nblk(N), BAMG_BLK, s, N, row_ptr, col_idx, val, (const ChainGeo*)dg, 1, hr[1], colsum, cnt,
+               err);
         LAUNCH(k_check_colsum, nblk(N), BAMG_BLK, s, N, colsum, err);
         int e = 0;
         HIPCHK(hipMemcpyAsync(&e, err, sizeof(int), hipMemcpyDeviceToHost, s));

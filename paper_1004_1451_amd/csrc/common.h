@@ -72,3 +72,26 @@ __device__ __forceinline__ T block_sum(T v, T* sh) {
 }
 
 __host__ __device__ __forceinline__ int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// Several chains are handled as one block-diagonal system: on every level the
+// rows of chain c form the range [off, off + n).  Chains are ordered by depth
+// (deepest first), so the chains that continue to the next level always form
+// a prefix of the rows.  One record per chain and level:
+struct ChainGeo {
+    int off, n;             // rows of this chain on this level
+    int nx, ny, periodic;   // its grid (state s = a*ny + b, local numbering)
+    FastDiv dy;             // division by ny
+    int coff, cn;           // its rows on the next level (cn = 0: coarsest here)
+    int ncx, ncy;           // next-level grid
+    FastDiv dcy;            // division by ncy
+};
+
+// Chain owning row i (the records are sorted by off; nch >= 1).
+__device__ __forceinline__ int find_chain(const ChainGeo* __restrict__ g, int nch, int i) {
+    int lo = 0, hi = nch - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (g[mid].off <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}

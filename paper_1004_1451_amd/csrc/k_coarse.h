@@ -1,0 +1,752 @@
+// Coarsest level of every chain, batched: blockIdx.y (or a loop) selects the
+// chain.  Each chain has exactly one coarsest level (at its own depth); the
+// descriptor below locates its operator inside that level's arrays and its
+// dense / vector storage inside the pools.
+//
+// Per chain (n = n_L, Section 4.2 and Algorithm 3 with l = L):
+//   W  = B_L^+ (n x n, row-major)         formed from the block LU of the
+//        padded operator [[B_11, 0], [0, 1]] (block tridiagonal in grid rows,
+//        blocks of b = ny <= 64, plus the corner blocks when periodic), then
+//        W = Pi_y [[B_11^-1, 0], [0, 0]] Pi_1;
+//   y  spans null(B_L); c = T_L^T 1; cy = c^T y;
+//   Arnoldi on v -> u - y (c^T u)/cy, u = W T_L v, for the coarsest
+//   eigenpairs.
+#pragma once
+#include "common.h"
+#include "k_dense.h"
+
+struct CoarseDesc {
+    int n, nx, ny, periodic;
+    int row0;                 // first row of the chain on its coarsest level
+    int voff;                 // offset of its length-n vectors in the vector pools
+    long long woff;           // offset of its n x n block in the W pool
+    long long boff;           // offset of its block-LU factors (5 * nx * ny^2)
+    long long aoff;           // offset of its Arnoldi basis (n * (am + 1))
+    int am;                   // Arnoldi steps (0: no eigenpairs)
+    FastDiv dy;
+    const int* brp; const int* bci; const void* bv;   // CSR of B on that level
+    const int* trp; const int* tci; const void* tv;   // CSR of T (null: T = I)
+};
+
+// ---------------------------------------------------------------- densify
+// W[i, j] = B_L[i, j] (W and bcol zeroed first); column n-1 also saved in bcol.
+template <typename M>
+__global__ void k_cz_densify(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, double* __restrict__ bcolp) {
+    const CoarseDesc d = cd[blockIdx.y];
+    double* W = Wp + d.woff;
+    const M* v = (const M*)d.bv;
+    for (int li = blockIdx.x * BAMG_BLK + threadIdx.x; li < d.n; li += gridDim.x * BAMG_BLK) {
+        const int i = d.row0 + li;
+        for (int p = d.brp[i]; p < d.brp[i + 1]; ++p) {
+            const int lj = d.bci[p] - d.row0;
+            W[(size_t)li * d.n + lj] = (double)v[p];
+            if (lj == d.n - 1) bcolp[d.voff + li] = (double)v[p];
+        }
+    }
+}
+
+// max |B_L| per chain (one block per chain) -> scale[chain].
+__global__ void k_cz_absmax(const CoarseDesc* __restrict__ cd, const double* __restrict__ Wp, double* __restrict__ scale) {
+    __shared__ double sh[BAMG_BLK];
+    const CoarseDesc d = cd[blockIdx.y];
+    const double* W = Wp + d.woff;
+    double m = 0;
+    for (long long e = threadIdx.x; e < (long long)d.n * d.n; e += BAMG_BLK) m = fmax(m, fabs(W[e]));
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = BAMG_BLK / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) scale[blockIdx.y] = sh[0];
+}
+
+// ---------------------------------------------------------------- block LU
+// Block storage of chain d: Dk | Up | Lo | Cl | Rw, each nx blocks of b x b.
+__device__ __forceinline__ double* cz_blk(double* base, const CoarseDesc& d, int part, int k) {
+    const long long bb = (long long)d.ny * d.ny;
+    return base + d.boff + ((long long)part * d.nx + k) * bb;
+}
+
+// Extract the blocks of the padded operator from the dense B_L (in W).
+__global__ void k_cz_extract(const CoarseDesc* __restrict__ cd, const double* __restrict__ Wp, double* __restrict__ Fp) {
+    const CoarseDesc d = cd[blockIdx.z];
+    const int k = blockIdx.y;
+    const int nx = d.nx, b = d.ny, K = nx - 1, n = d.n, bb = b * b;
+    if (k >= nx) return;
+    const bool arrow = d.periodic && nx >= 3;
+    const double* A = Wp + d.woff;
+    for (int kind = 0; kind < 5; ++kind) {
+        int bi, bj;
+        if (kind == 0) { bi = k; bj = k; }
+        else if (kind == 1) { if (k >= K) continue; bi = k; bj = k + 1; }
+        else if (kind == 2) { if (k < 1) continue; bi = k; bj = k - 1; }
+        else if (kind == 3) { if (!arrow || k >= K - 1) continue; bi = k; bj = K; }
+        else { if (!arrow || k >= K - 1) continue; bi = K; bj = k; }
+        double* dst = cz_blk(Fp, d, kind, k);
+        for (int e = blockIdx.x * BAMG_BLK + threadIdx.x; e < bb; e += gridDim.x * BAMG_BLK) {
+            int r = e / b, c = e % b;
+            int gi = bi * b + r, gj = bj * b + c;
+            double v = A[(size_t)gi * n + gj];
+            if (gi == n - 1 || gj == n - 1) v = (gi == gj) ? 1.0 : 0.0;
+            dst[e] = v;
+        }
+    }
+}
+
+// Invert diagonal block k of every chain with k < nx (k < 0: the chain's
+// last block).  One workgroup per chain; same Gauss-Jordan as k_gj_diag.
+__global__ void __launch_bounds__(BAMG_BLK)
+k_cz_diag(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, const double* __restrict__ scale,
+          double* __restrict__ minpiv) {
+    const CoarseDesc d = cd[blockIdx.x];
+    const int kk = k < 0 ? d.nx - 1 : k;
+    if (kk >= d.nx - (k < 0 ? 0 : 1) || d.n < 2) return;
+    __shared__ double M[2][GJ_NB][GJ_NB + 1];
+    double* A = cz_blk(Fp, d, 0, kk);
+    const int nb = d.ny;
+    const int tid = threadIdx.x;
+    const int r0 = (tid / 16) * 4, c0 = (tid % 16) * 4;
+    double S[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            int r = r0 + a, c = c0 + b;
+            S[a][b] = (r < nb && c < nb) ? A[r * nb + c] : (r == c ? 1.0 : 0.0);
+            M[0][r][c] = S[a][b];
+        }
+    const double sc = scale[blockIdx.x];
+    double mp = 1e300;
+    __syncthreads();
+    for (int st = 0; st < GJ_NB; ++st) {
+        const int rd = st & 1, wr = rd ^ 1;
+        const double piv = M[rd][st][st];
+        const double ip = 1.0 / piv;
+        if (tid == 0 && st < nb) mp = fmin(mp, fabs(piv) / sc);
+        double f[4], pr[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) f[a] = M[rd][r0 + a][st];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) pr[b] = M[rd][st][c0 + b] * ip;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const bool rk = (r0 + a) == st, ck = (c0 + b) == st;
+                double v = S[a][b] - f[a] * pr[b];
+                v = ck ? -f[a] * ip : v;
+                v = rk ? pr[b] : v;
+                v = (rk && ck) ? ip : v;
+                S[a][b] = v;
+                M[wr][r0 + a][c0 + b] = v;
+            }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            int r = r0 + a, c = c0 + b;
+            if (r < nb && c < nb) A[r * nb + c] = S[a][b];
+        }
+    if (tid == 0) minpiv[blockIdx.x] = fmin(minpiv[blockIdx.x], mp);
+}
+
+// One b x b product C = A B (mode 0, C may alias A) or C -= A B (mode 1).
+__device__ void cz_gemm(int b, const double* A, const double* Bm, double* C, int mode, double (*AsT)[GJ_NB + 2],
+                        double (*Bs)[GJ_NB + 2]) {
+    const int tid = threadIdx.x;
+    for (int e = tid; e < GJ_NB * GJ_NB; e += BAMG_BLK) {
+        int r = e / GJ_NB, c = e % GJ_NB;
+        bool ok = r < b && c < b;
+        AsT[c][r] = ok ? A[r * b + c] : 0.0;
+        Bs[r][c] = ok ? Bm[r * b + c] : 0.0;
+    }
+    __syncthreads();
+    const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+    for (int t = 0; t < b; ++t) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) av[a] = AsT[t][tr + a];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bv[c] = Bs[t][tc + c];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[a][c] += av[a] * bv[c];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            int r = tr + a, cc = tc + c;
+            if (r < b && cc < b) {
+                if (mode == 0) C[r * b + cc] = acc[a][c];
+                else C[r * b + cc] -= acc[a][c];
+            }
+        }
+}
+
+// Elimination of block column k for every chain with k < K = nx - 1.
+// phase 0: multipliers  Lo[k+1] = Lo[k+1] Dinv_k  (and Rw[k] = Rw[k] Dinv_k);
+// phase 1: updates of the blocks in rows {k+1, K} x columns {k+1, K}.
+// blockIdx.x = product (0..3), blockIdx.y = chain.
+__global__ void __launch_bounds__(BAMG_BLK)
+k_cz_elim(const CoarseDesc* __restrict__ cd, int k, int phase, double* __restrict__ Fp) {
+    __shared__ double AsT[GJ_NB][GJ_NB + 2];
+    __shared__ double Bs[GJ_NB][GJ_NB + 2];
+    const CoarseDesc d = cd[blockIdx.y];
+    const int K = d.nx - 1, q = blockIdx.x;
+    if (k >= K || d.n < 2) return;
+    const bool arrow = d.periodic && d.nx >= 3;
+    const int b = d.ny;
+    const double *A = nullptr, *Bm = nullptr;
+    double* C = nullptr;
+    int mode = 1;
+    if (k + 1 < K) {
+        if (phase == 0) {
+            if (q == 0) { A = cz_blk(Fp, d, 2, k + 1); Bm = cz_blk(Fp, d, 0, k); C = cz_blk(Fp, d, 2, k + 1); mode = 0; }
+            else if (q == 1 && arrow) { A = cz_blk(Fp, d, 4, k); Bm = cz_blk(Fp, d, 0, k); C = cz_blk(Fp, d, 4, k); mode = 0; }
+        } else {
+            if (q == 0) { A = cz_blk(Fp, d, 2, k + 1); Bm = cz_blk(Fp, d, 1, k); C = cz_blk(Fp, d, 0, k + 1); }
+            else if (arrow && q == 1) {
+                A = cz_blk(Fp, d, 2, k + 1); Bm = cz_blk(Fp, d, 3, k);
+                C = (k + 1 < K - 1) ? cz_blk(Fp, d, 3, k + 1) : cz_blk(Fp, d, 1, k + 1);
+            } else if (arrow && q == 2) {
+                A = cz_blk(Fp, d, 4, k); Bm = cz_blk(Fp, d, 1, k);
+                C = (k + 1 < K - 1) ? cz_blk(Fp, d, 4, k + 1) : cz_blk(Fp, d, 2, K);
+            } else if (arrow && q == 3) {
+                A = cz_blk(Fp, d, 4, k); Bm = cz_blk(Fp, d, 3, k); C = cz_blk(Fp, d, 0, K);
+            }
+        }
+    } else {   // k + 1 == K: row K is row k + 1
+        if (phase == 0 && q == 0) { A = cz_blk(Fp, d, 2, K); Bm = cz_blk(Fp, d, 0, k); C = cz_blk(Fp, d, 2, K); mode = 0; }
+        if (phase == 1 && q == 0) { A = cz_blk(Fp, d, 2, K); Bm = cz_blk(Fp, d, 1, k); C = cz_blk(Fp, d, 0, K); }
+    }
+    if (!C) return;
+    cz_gemm(b, A, Bm, C, mode, AsT, Bs);
+}
+
+// W = I on every chain's block.
+__global__ void k_cz_identity(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp) {
+    const CoarseDesc d = cd[blockIdx.y];
+    double* W = Wp + d.woff;
+    const long long nn = (long long)d.n * d.n;
+    for (long long e = (long long)blockIdx.x * BAMG_BLK + threadIdx.x; e < nn; e += (long long)gridDim.x * BAMG_BLK)
+        W[e] = (e / d.n == e % d.n) ? 1.0 : 0.0;
+}
+
+// Block substitution step for every chain (blockIdx.y), column tile
+// blockIdx.x (64 columns):  T = W[kout] - A1 W[j1] - A2 W[j2], then
+// W[kout] = Dinv T.  The operands of each chain follow from (phase, step):
+//   phase 0 (forward, step s >= 1):   kout = s (s < K): A1 = Lo[s], j1 = s-1
+//   phase 1 (forward arrow, j = 2s):  kout = K: A1 = Rw[j], A2 = Rw[j+1]  (j < K-1)
+//   phase 2 (forward last row):       kout = K: A1 = Lo[K], j1 = K-1
+//   phase 3 (backward last row):      kout = K: Dinv_K
+//   phase 4 (backward, step s):       kout = K-1-s: A1 = Up, j1 = kout+1,
+//                                      A2 = Cl (arrow, kout < K-1), j2 = K; Dinv
+__global__ void __launch_bounds__(BAMG_BLK)
+k_cz_strip(const CoarseDesc* __restrict__ cd, int phase, int step, double* __restrict__ Wp,
+           const double* __restrict__ Fp) {
+    __shared__ double Ms[GJ_NB][GJ_NB + 1];
+    __shared__ double Xs[GJ_NB][64 + 1];
+    const CoarseDesc d = cd[blockIdx.y];
+    const int K = d.nx - 1, b = d.ny, n = d.n;
+    const bool arrow = d.periodic && d.nx >= 3;
+    int kout = -1, j1 = 0, j2 = 0;
+    const double *A1 = nullptr, *A2 = nullptr, *Dinv = nullptr;
+    double* F = (double*)Fp;
+    if (n < 2) return;
+    if (phase == 0) {
+        if (step >= 1 && step < K) { kout = step; A1 = cz_blk(F, d, 2, step); j1 = step - 1; }
+    } else if (phase == 1) {
+        const int j = 2 * step;
+        if (arrow && j < K - 1) {
+            kout = K; A1 = cz_blk(F, d, 4, j); j1 = j;
+            if (j + 1 < K - 1) { A2 = cz_blk(F, d, 4, j + 1); j2 = j + 1; }
+        }
+    } else if (phase == 2) {
+        if (K >= 1) { kout = K; A1 = cz_blk(F, d, 2, K); j1 = K - 1; }
+    } else if (phase == 3) {
+        kout = K; Dinv = cz_blk(F, d, 0, K);
+    } else {
+        const int k = K - 1 - step;
+        if (k >= 0) {
+            kout = k; A1 = cz_blk(F, d, 1, k); j1 = k + 1; Dinv = cz_blk(F, d, 0, k);
+            if (arrow && k < K - 1) { A2 = cz_blk(F, d, 3, k); j2 = K; }
+        }
+    }
+    const int c0 = blockIdx.x * 64;
+    if (kout < 0 || c0 >= n) return;
+    double* W = Wp + d.woff;
+    const int tid = threadIdx.x;
+    const int w = min(64, n - c0);
+    const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+    double T[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int r = tr + a, c = tc + q;
+            T[a][q] = (r < b && c < w) ? W[(size_t)(kout * b + r) * n + c0 + c] : 0.0;
+        }
+    for (int term = 0; term < 2; ++term) {
+        const double* M = term == 0 ? A1 : A2;
+        const int jb = term == 0 ? j1 : j2;
+        if (!M) continue;
+        __syncthreads();
+        for (int e = tid; e < b * b; e += BAMG_BLK) Ms[e / b][e % b] = M[e];
+        for (int e = tid; e < b * 64; e += BAMG_BLK) {
+            int r = e / 64, c = e % 64;
+            Xs[r][c] = c < w ? W[(size_t)(jb * b + r) * n + c0 + c] : 0.0;
+        }
+        __syncthreads();
+        for (int t = 0; t < b; ++t) {
+            double mv[4], xv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) mv[a] = (tr + a < b) ? Ms[tr + a][t] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xv[q] = Xs[t][tc + q];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) T[a][q] -= mv[a] * xv[q];
+        }
+    }
+    if (Dinv) {
+        __syncthreads();
+        for (int e = tid; e < b * b; e += BAMG_BLK) Ms[e / b][e % b] = Dinv[e];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Xs[tr + a][tc + q] = T[a][q];
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) T[a][q] = 0.0;
+        for (int t = 0; t < b; ++t) {
+            double mv[4], xv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) mv[a] = (tr + a < b) ? Ms[tr + a][t] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xv[q] = Xs[t][tc + q];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) T[a][q] += mv[a] * xv[q];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int r = tr + a, c = tc + q;
+            if (r < b && c < w) W[(size_t)(kout * b + r) * n + c0 + c] = T[a][q];
+        }
+}
+
+// ---------------------------------------------------------------- projections
+// Zero the last row and column of W (the padding).
+__global__ void k_cz_zero_border(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp) {
+    const CoarseDesc d = cd[blockIdx.y];
+    double* W = Wp + d.woff;
+    for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < d.n; i += gridDim.x * BAMG_BLK) {
+        W[(size_t)(d.n - 1) * d.n + i] = 0.0;
+        W[(size_t)i * d.n + d.n - 1] = 0.0;
+    }
+}
+
+// out[voff + i] = sum_j W[i, j] x[voff + j] (i < rows(d), j < cols(d)):
+// one wavefront per row.  which = 0: rows = cols = n; 1: rows = cols = n-1.
+__global__ void __launch_bounds__(BAMG_BLK)
+k_cz_gemv(const CoarseDesc* __restrict__ cd, int which, const double* __restrict__ Wp, const double* __restrict__ x,
+          double* __restrict__ out) {
+    const CoarseDesc d = cd[blockIdx.y];
+    const int m = which ? d.n - 1 : d.n;
+    const double* W = Wp + d.woff;
+    const int lane = threadIdx.x % BAMG_WAVE;
+    for (int row = blockIdx.x * (BAMG_BLK / BAMG_WAVE) + threadIdx.x / BAMG_WAVE; row < m;
+         row += gridDim.x * (BAMG_BLK / BAMG_WAVE)) {
+        const double* a = W + (size_t)row * d.n;
+        double s = 0;
+        for (int j = lane; j < m; j += BAMG_WAVE) s += a[j] * x[d.voff + j];
+        s = wave_sum(s);
+        if (lane == 0) out[d.voff + row] = s;
+    }
+}
+
+// FP32 copy of the same product for the mixed-precision cycle (vector in
+// the level's FP32 cycle buffer at row0).
+__global__ void __launch_bounds__(BAMG_BLK)
+k_cz_gemv_f32(const CoarseDesc* __restrict__ cd, const float* __restrict__ Wp, const float* __restrict__ x,
+              float* __restrict__ out) {
+    const CoarseDesc d = cd[blockIdx.y];
+    const float* W = Wp + d.woff;
+    const int lane = threadIdx.x % BAMG_WAVE;
+    for (int row = blockIdx.x * (BAMG_BLK / BAMG_WAVE) + threadIdx.x / BAMG_WAVE; row < d.n;
+         row += gridDim.x * (BAMG_BLK / BAMG_WAVE)) {
+        const float* a = W + (size_t)row * d.n;
+        float s = 0;
+        for (int j = lane; j < d.n; j += BAMG_WAVE) s += a[j] * x[d.row0 + j];
+        s = wave_sum(s);
+        if (lane == 0) out[d.row0 + row] = s;
+    }
+}
+
+// FP64 coarse solve inside the cycle: e[row0 + i] = sum_j W[i, j] f[row0 + j].
+__global__ void __launch_bounds__(BAMG_BLK)
+k_cz_gemv_rows(const CoarseDesc* __restrict__ cd, const double* __restrict__ Wp, const double* __restrict__ x,
+               double* __restrict__ out) {
+    const CoarseDesc d = cd[blockIdx.y];
+    const double* W = Wp + d.woff;
+    const int lane = threadIdx.x % BAMG_WAVE;
+    for (int row = blockIdx.x * (BAMG_BLK / BAMG_WAVE) + threadIdx.x / BAMG_WAVE; row < d.n;
+         row += gridDim.x * (BAMG_BLK / BAMG_WAVE)) {
+        const double* a = W + (size_t)row * d.n;
+        double s = 0;
+        for (int j = lane; j < d.n; j += BAMG_WAVE) s += a[j] * x[d.row0 + j];
+        s = wave_sum(s);
+        if (lane == 0) out[d.row0 + row] = s;
+    }
+}
+
+// u = y^T W per chain: column-chunk partials then a fixed-order final.
+__global__ void k_cz_gemv_t_partial(const CoarseDesc* __restrict__ cd, const double* __restrict__ Wp,
+                                    const double* __restrict__ y, double* __restrict__ part, int RCH) {
+    const CoarseDesc d = cd[blockIdx.z];
+    const int j = blockIdx.x * BAMG_BLK + threadIdx.x;
+    const int r0 = blockIdx.y * RCH;
+    if (j >= d.n || r0 >= d.n) return;
+    const double* W = Wp + d.woff;
+    double s = 0;
+    const int r1 = min(d.n, r0 + RCH);
+    for (int i = r0; i < r1; ++i) s += y[d.voff + i] * W[(size_t)i * d.n + j];
+    part[(long long)gridDim.y * d.voff + (long long)blockIdx.y * d.n + j] = s;
+}
+
+__global__ void k_cz_gemv_t_final(const CoarseDesc* __restrict__ cd, int nchunk_max, int RCH,
+                                  const double* __restrict__ part, double* __restrict__ out) {
+    const CoarseDesc d = cd[blockIdx.y];
+    const int j = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (j >= d.n) return;
+    const int nchunks = (d.n + RCH - 1) / RCH;
+    double s = 0;
+    for (int c = 0; c < nchunks; ++c) s += part[(long long)nchunk_max * d.voff + (long long)c * d.n + j];
+    out[d.voff + j] = s;
+}
+
+// Per-chain dot product of two pooled vectors -> out[chain] (one block each).
+__global__ void k_cz_dot(const CoarseDesc* __restrict__ cd, const double* __restrict__ a, const double* __restrict__ b,
+                         double* __restrict__ out, int stride) {
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    const CoarseDesc d = cd[blockIdx.x];
+    double s = 0;
+    for (int i = threadIdx.x; i < d.n; i += BAMG_BLK) s += a[d.voff + i] * b[d.voff + i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[(size_t)blockIdx.x * stride] = s;
+}
+
+// y_1 = -g, y_n = 1 (g = Binv b_col).
+__global__ void k_cz_null(const CoarseDesc* __restrict__ cd, const double* __restrict__ g, double* __restrict__ y) {
+    const CoarseDesc d = cd[blockIdx.y];
+    for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < d.n; i += gridDim.x * BAMG_BLK)
+        y[d.voff + i] = (i < d.n - 1) ? -g[d.voff + i] : 1.0;
+}
+
+// W <- W - s 1^T / n - y (u - (y^T s) 1^T / n)^T / (y^T y), with
+// sc[chain*SCS + 0] = y^T s, sc[chain*SCS + 1] = y^T y.
+__global__ void k_cz_project(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const double* __restrict__ s,
+                             const double* __restrict__ u, const double* __restrict__ y, const double* __restrict__ sc,
+                             int SCS) {
+    const CoarseDesc d = cd[blockIdx.y];
+    double* W = Wp + d.woff;
+    const double inv_n = 1.0 / d.n;
+    const double ys = sc[(size_t)blockIdx.y * SCS], yy = sc[(size_t)blockIdx.y * SCS + 1];
+    const long long nn = (long long)d.n * d.n;
+    for (long long e = (long long)blockIdx.x * BAMG_BLK + threadIdx.x; e < nn; e += (long long)gridDim.x * BAMG_BLK) {
+        int i = (int)(e / d.n), j = (int)(e % d.n);
+        W[e] = W[e] - s[d.voff + i] * inv_n - y[d.voff + i] * (u[d.voff + j] - ys * inv_n) / yy;
+    }
+}
+
+// c_j = sum_i T_L[i, j] (T = I: c = 1), gathered from the 3x3 box rows in
+// ascending row order.
+template <typename M>
+__global__ void k_cz_colsum(const CoarseDesc* __restrict__ cd, double* __restrict__ c) {
+    const CoarseDesc d = cd[blockIdx.y];
+    for (int j = blockIdx.x * BAMG_BLK + threadIdx.x; j < d.n; j += gridDim.x * BAMG_BLK) {
+        if (!d.trp) { c[d.voff + j] = 1.0; continue; }
+        const M* tv = (const M*)d.tv;
+        int ja = (int)d.dy.div((uint32_t)j), jb = j - ja * d.ny;
+        int rows[9];
+#pragma unroll
+        for (int s = 0; s < 9; ++s) {
+            int a = ja + s / 3 - 1, b = jb + s % 3 - 1;
+            rows[s] = -1;
+            if (d.periodic) {
+                a = a < 0 ? a + d.nx : (a >= d.nx ? a - d.nx : a);
+                b = b < 0 ? b + d.ny : (b >= d.ny ? b - d.ny : b);
+            } else if (a < 0 || a >= d.nx || b < 0 || b >= d.ny) {
+                continue;
+            }
+            rows[s] = a * d.ny + b;
+        }
+        double sum = 0;
+        for (int pass = 0; pass < 9; ++pass) {
+            int best = -1;
+            for (int t = 0; t < 9; ++t) {
+                if (rows[t] < 0) continue;
+                int rank = 0;
+                for (int u = 0; u < 9; ++u) rank += rows[u] >= 0 && rows[u] < rows[t];
+                if (rank == pass) best = rows[t];
+            }
+            if (best < 0) break;
+            const int gi = d.row0 + best;
+            for (int p = d.trp[gi]; p < d.trp[gi + 1]; ++p)
+                if (d.tci[p] == d.row0 + j) sum += (double)tv[p];
+        }
+        c[d.voff + j] = sum;
+    }
+}
+
+// ---------------------------------------------------------------- Arnoldi
+// Basis of chain d: Vb[aoff + j*n + i], j <= am.  Steps run in lockstep over
+// the chains; a chain with j >= am (or no eigenpairs) is idle.
+// start vector: seeded u - 1/2, then projected onto {c^T v = 0}.
+__global__ void k_cz_arn_start(const CoarseDesc* __restrict__ cd, uint64_t seed, double* __restrict__ Vb) {
+    const CoarseDesc d = cd[blockIdx.y];
+    if (d.am < 1) return;
+    for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < d.n; i += gridDim.x * BAMG_BLK)
+        Vb[d.aoff + i] = splitmix_u01(seed, 7ull, (uint64_t)i) - 0.5;
+}
+
+// w = T v_j (pooled vector tmp), for chains with j < am.
+template <typename M>
+__global__ void k_cz_tv(const CoarseDesc* __restrict__ cd, int j, const double* __restrict__ Vb, double* __restrict__ w) {
+    const CoarseDesc d = cd[blockIdx.y];
+    if (j >= d.am) return;
+    const double* v = Vb + d.aoff + (size_t)j * d.n;
+    for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < d.n; i += gridDim.x * BAMG_BLK) {
+        double s;
+        if (!d.trp) {
+            s = v[i];
+        } else {
+            const M* tv = (const M*)d.tv;
+            s = 0;
+            const int gi = d.row0 + i;
+            for (int p = d.trp[gi]; p < d.trp[gi + 1]; ++p) s += (double)tv[p] * v[d.tci[p] - d.row0];
+        }
+        w[d.voff + i] = s;
+    }
+}
+
+// u = W w into basis column j+1 (a GEMV per chain).
+__global__ void __launch_bounds__(BAMG_BLK)
+k_cz_arn_gemv(const CoarseDesc* __restrict__ cd, int j, const double* __restrict__ Wp, const double* __restrict__ w,
+              double* __restrict__ Vb) {
+    const CoarseDesc d = cd[blockIdx.y];
+    if (j >= d.am) return;
+    const double* W = Wp + d.woff;
+    double* u = Vb + d.aoff + (size_t)(j + 1) * d.n;
+    const int lane = threadIdx.x % BAMG_WAVE;
+    for (int row = blockIdx.x * (BAMG_BLK / BAMG_WAVE) + threadIdx.x / BAMG_WAVE; row < d.n;
+         row += gridDim.x * (BAMG_BLK / BAMG_WAVE)) {
+        const double* a = W + (size_t)row * d.n;
+        double s = 0;
+        for (int q = lane; q < d.n; q += BAMG_WAVE) s += a[q] * w[d.voff + q];
+        s = wave_sum(s);
+        if (lane == 0) u[row] = s;
+    }
+}
+
+// dots[chain*DS + b] = <x_b, u> for basis columns b <= nb (x_0 = c when
+// with_c: then only one dot, <c, u>).  One block per (b, chain).
+__global__ void k_cz_arn_dots(const CoarseDesc* __restrict__ cd, int j, int with_c, const double* __restrict__ cvec,
+                              const double* __restrict__ Vb, double* __restrict__ dots, int DS) {
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    const CoarseDesc d = cd[blockIdx.y];
+    const int b = blockIdx.x;
+    if (j >= d.am || (with_c ? b > 0 : b > j)) return;
+    const double* u = Vb + d.aoff + (size_t)(j + 1) * d.n;
+    const double* x = with_c ? cvec + d.voff : Vb + d.aoff + (size_t)b * d.n;
+    double s = 0;
+    for (int i = threadIdx.x; i < d.n; i += BAMG_BLK) s += x[i] * u[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) dots[(size_t)blockIdx.y * DS + b] = s;
+}
+
+// mode 0: u -= y * dots[0] / cy;  mode 1: u -= sum_{b<=j} dots[b] v_b and
+// H[0..j, j] += dots (H: chain stride HS, column-major ld am+1).
+__global__ void k_cz_arn_update(const CoarseDesc* __restrict__ cd, int j, int mode, const double* __restrict__ y,
+                                const double* __restrict__ cy, const double* __restrict__ dots, int DS,
+                                double* __restrict__ Vb, double* __restrict__ H, int HS) {
+    const CoarseDesc d = cd[blockIdx.y];
+    if (j >= d.am) return;
+    const double* dt = dots + (size_t)blockIdx.y * DS;
+    double* u = Vb + d.aoff + (size_t)(j + 1) * d.n;
+    for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < d.n; i += gridDim.x * BAMG_BLK) {
+        double s = u[i];
+        if (mode == 0) {
+            s -= y[d.voff + i] * (dt[0] / cy[blockIdx.y]);
+        } else {
+            for (int b = 0; b <= j; ++b) s -= dt[b] * Vb[d.aoff + (size_t)b * d.n + i];
+        }
+        u[i] = s;
+    }
+    if (mode == 1 && blockIdx.x == 0 && (int)threadIdx.x <= j)
+        H[(size_t)blockIdx.y * HS + (size_t)j * (d.am + 1) + threadIdx.x] += dt[threadIdx.x];
+}
+
+// Normalise basis column j+1 (or column 0 with j = -1): v = u / ||u||,
+// H[j+1, j] = ||u||.  One block per chain (fixed-order norm).
+__global__ void k_cz_arn_normalize(const CoarseDesc* __restrict__ cd, int j, double* __restrict__ Vb,
+                                   double* __restrict__ H, int HS) {
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    __shared__ double nrm;
+    const CoarseDesc d = cd[blockIdx.x];
+    if (j >= d.am || d.am < 1) return;
+    double* u = Vb + d.aoff + (size_t)(j + 1) * d.n;
+    double s = 0;
+    for (int i = threadIdx.x; i < d.n; i += BAMG_BLK) s += u[i] * u[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) {
+        nrm = sqrt(s);
+        if (j >= 0) H[(size_t)blockIdx.x * HS + (size_t)j * (d.am + 1) + j + 1] = nrm;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < d.n; i += BAMG_BLK) u[i] = nrm > 0 ? u[i] / nrm : 0.0;
+}
+
+// Ritz vector of entry e of chain (blockIdx.y): v = Vb[:, 0:am] s_e.
+__global__ void k_cz_ritz(const CoarseDesc* __restrict__ cd, int e, const int* __restrict__ nsel, int NS,
+                          const double* __restrict__ Vb, const double* __restrict__ sel_s, int SS,
+                          double* __restrict__ rre, double* __restrict__ rim) {
+    const CoarseDesc d = cd[blockIdx.y];
+    if (e >= nsel[(size_t)blockIdx.y * NS]) return;
+    const double* s = sel_s + (size_t)blockIdx.y * SS + (size_t)e * 2 * d.am;
+    for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < d.n; i += gridDim.x * BAMG_BLK) {
+        double a = 0, b = 0;
+        for (int j = 0; j < d.am; ++j) {
+            double v = Vb[d.aoff + (size_t)j * d.n + i];
+            a += v * s[2 * j]; b += v * s[2 * j + 1];
+        }
+        rre[d.voff + i] = a; rim[d.voff + i] = b;
+    }
+}
+
+// Normalise entry e's Ritz vector (||v|| = 1, largest-modulus entry real
+// positive, lowest index on ties) into its column(s) of the chain's V rows
+// (row0 .. on its coarsest level, row stride VS).  One block per chain.
+template <typename T>
+__global__ void k_cz_eigvec(const CoarseDesc* __restrict__ cd, int e, const int* __restrict__ nsel, int NS,
+                            const double* __restrict__ sel_lam, int LS, const double* __restrict__ rre,
+                            const double* __restrict__ rim, const int* __restrict__ ent_col, int KV,
+                            T* __restrict__ V, int VS) {
+    __shared__ double sh[BAMG_BLK];
+    __shared__ int shi[BAMG_BLK];
+    __shared__ double shs[BAMG_BLK / BAMG_WAVE];
+    __shared__ double fac[2];
+    const CoarseDesc d = cd[blockIdx.x];
+    if (e >= nsel[(size_t)blockIdx.x * NS]) return;
+    const bool pair = sel_lam[(size_t)blockIdx.x * LS + 2 * e + 1] != 0.0;
+    const int c = ent_col[(size_t)blockIdx.x * KV + e + 1];
+    const double* vr = rre + d.voff;
+    const double* vi = rim + d.voff;
+    double s = 0, best = -1;
+    int bi = 0;
+    for (int i = threadIdx.x; i < d.n; i += BAMG_BLK) {
+        double m2 = vr[i] * vr[i] + (pair ? vi[i] * vi[i] : 0.0);
+        s += m2;
+        if (m2 > best) { best = m2; bi = i; }
+    }
+    s = block_sum(s, shs);
+    __syncthreads();
+    sh[threadIdx.x] = best; shi[threadIdx.x] = bi;
+    __syncthreads();
+    for (int st = BAMG_BLK / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            double o = sh[threadIdx.x + st];
+            int oi = shi[threadIdx.x + st];
+            if (o > sh[threadIdx.x] || (o == sh[threadIdx.x] && oi < shi[threadIdx.x])) { sh[threadIdx.x] = o; shi[threadIdx.x] = oi; }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        int im = shi[0];
+        double ar = vr[im], ai = pair ? vi[im] : 0.0;
+        double mod = sqrt(ar * ar + ai * ai);
+        double nrm = sqrt(s);
+        fac[0] = ar / mod / nrm; fac[1] = -ai / mod / nrm;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < d.n; i += BAMG_BLK) {
+        double a = vr[i], b = pair ? vi[i] : 0.0;
+        double nr = a * fac[0] - b * fac[1], ni = a * fac[1] + b * fac[0];
+        V[(size_t)(d.row0 + i) * VS + c] = (T)nr;
+        if (pair) V[(size_t)(d.row0 + i) * VS + c + 1] = (T)ni;
+    }
+}
+
+// Column 0 of V: y / (c^T y).
+template <typename T>
+__global__ void k_cz_ycol(const CoarseDesc* __restrict__ cd, const double* __restrict__ y, const double* __restrict__ cy,
+                          T* __restrict__ V, int VS) {
+    const CoarseDesc d = cd[blockIdx.y];
+    for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < d.n; i += gridDim.x * BAMG_BLK)
+        V[(size_t)(d.row0 + i) * VS] = (T)(y[d.voff + i] / cy[blockIdx.y]);
+}
+
+// Eigenvalue / column tables of every chain from its selection (one thread
+// per chain): lam[chain][2*KV], kind[chain][KV], ent_col[chain][KV],
+// nvc[chain], nentc[chain].
+__global__ void k_cz_tables(int nch, const int* __restrict__ nsel, int NS, const double* __restrict__ sel_lam, int LS,
+                            double* __restrict__ lamall, int* __restrict__ kindall, int* __restrict__ ent_colall,
+                            int KV, int* __restrict__ nvc, int* __restrict__ nentc) {
+    int ch = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ch >= nch) return;
+    double* lam = lamall + (size_t)ch * 2 * KV;
+    int* kind = kindall + (size_t)ch * KV;
+    int* ent_col = ent_colall + (size_t)ch * KV;
+    for (int q = 0; q < 2 * KV; ++q) lam[q] = 0.0;
+    for (int q = 0; q < KV; ++q) { kind[q] = 0; ent_col[q] = 0; }
+    int ne = nsel[(size_t)ch * NS];
+    int c = 1;
+    for (int e = 0; e < ne; ++e) {
+        double lr = sel_lam[(size_t)ch * LS + 2 * e], li = sel_lam[(size_t)ch * LS + 2 * e + 1];
+        ent_col[e + 1] = c;
+        if (li != 0.0) {
+            lam[2 * c] = lr; lam[2 * c + 1] = li; kind[c] = 1;
+            lam[2 * c + 2] = lr; lam[2 * c + 3] = li; kind[c + 1] = 2;
+            c += 2;
+        } else {
+            lam[2 * c] = lr; lam[2 * c + 1] = 0; kind[c] = 0;
+            c += 1;
+        }
+    }
+    nvc[ch] = c;
+    nentc[ch] = ne + 1;
+}
+
+// One wavefront per chain: eigenvalues of its Arnoldi Hessenberg matrix
+// (stride HS), selection and eigenvectors (see hessenberg_eig_body).
+// Chains without eigenpairs report no selection.
+__global__ void __launch_bounds__(BAMG_WAVE)
+k_cz_hess(const CoarseDesc* __restrict__ cd, int want, const double* __restrict__ Hh, int HS, double* __restrict__ Hrow,
+          int HRS, int* __restrict__ nsel, int NS, double* __restrict__ sel_lam, int LS, double* __restrict__ sel_s,
+          int SS) {
+    const int c = blockIdx.x;
+    const CoarseDesc d = cd[c];
+    if (d.am < 1 || want < 1) {
+        if (threadIdx.x == 0) { nsel[(size_t)c * NS] = 0; nsel[(size_t)c * NS + 1] = 0; nsel[(size_t)c * NS + 2] = 0; }
+        return;
+    }
+    hessenberg_eig_body(d.am, want, Hh + (size_t)c * HS, Hrow + (size_t)c * HRS, nsel + (size_t)c * NS,
+                        sel_lam + (size_t)c * LS, sel_s + (size_t)c * SS);
+}

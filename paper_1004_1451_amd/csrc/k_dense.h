@@ -764,9 +764,9 @@ __device__ void hess_shift_solve_wave(int m, const double* __restrict__ H, doubl
 //   sel_lam[2e..2e+1] = lam of entry e (Im >= 0 member of a pair);
 //   sel_s[e*2m + 2j..] = (re, im) of the eigenvector of H for entry e.
 // Hrow: scratch m*m doubles (row-major copy of H_m).
-__global__ void __launch_bounds__(BAMG_WAVE)
-k_hessenberg_eig(int m, int want, const double* __restrict__ Hh, double* __restrict__ Hrow,
-                 int* __restrict__ nsel_out, double* __restrict__ sel_lam, double* __restrict__ sel_s) {
+__device__ void hessenberg_eig_body(int m, int want, const double* __restrict__ Hh, double* __restrict__ Hrow,
+                                    int* __restrict__ nsel_out, double* __restrict__ sel_lam,
+                                    double* __restrict__ sel_s) {
     __shared__ double A[HQR_MAXM * HQR_LD];
     __shared__ double wr[HQR_MAXM], wi[HQR_MAXM], zr[HQR_MAXM], zi[HQR_MAXM];
     __shared__ int used[HQR_MAXM];

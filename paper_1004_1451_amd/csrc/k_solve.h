@@ -221,3 +221,206 @@ __global__ void k_f2d(int n, const float* __restrict__ a, double* __restrict__ b
     int i = blockIdx.x * BAMG_BLK + threadIdx.x;
     if (i < n) b[i] = (double)a[i];
 }
+
+// ---------------------------------------------------------------- per-chain (segmented) versions
+// Chain c owns rows [g[c].off, g[c].off + g[c].n) of the finest level; its
+// rows are split into gridDim.x fixed chunks.  Per-chain scalars live at
+// out[c * stride].
+
+template <int OP>
+__global__ void k_seg_reduce_partial(const ChainGeo* __restrict__ geo, const double* __restrict__ a,
+                                     const double* __restrict__ b, double* __restrict__ part) {
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    const ChainGeo g = geo[blockIdx.y];
+    const int chunk = (g.n + gridDim.x - 1) / gridDim.x;
+    const int r0 = g.off + blockIdx.x * chunk, r1 = min(g.off + g.n, r0 + chunk);
+    double s = 0;
+    for (int i = r0 + threadIdx.x; i < r1; i += BAMG_BLK) {
+        double v = a[i];
+        if (OP == RED_DOT) s += v * b[i];
+        else if (OP == RED_ABS) s += fabs(v);
+        else if (OP == RED_SUM) s += v;
+        else s += v < 0 ? -v : 0.0;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ void k_seg_reduce_final(int nparts, const double* __restrict__ part, double* __restrict__ out, int stride) {
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    double s = 0;
+    for (int j = threadIdx.x; j < nparts; j += BAMG_BLK) s += part[(size_t)blockIdx.x * nparts + j];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[(size_t)blockIdx.x * stride] = s;
+}
+
+// Multi-dots per chain: part[c][chunk*4 + wave][nv] (wave partials, no
+// block barrier); only chains with act[c] != 0.
+__global__ void __launch_bounds__(BAMG_BLK)
+k_seg_mdot_partial(const ChainGeo* __restrict__ geo, int N, int nv, const int* __restrict__ act,
+                   const double* __restrict__ V, const double* __restrict__ w, double* __restrict__ part) {
+    const ChainGeo g = geo[blockIdx.y];
+    if (!act[blockIdx.y]) return;
+    const int lane = threadIdx.x % BAMG_WAVE, wv = threadIdx.x / BAMG_WAVE;
+    const int chunk = (g.n + gridDim.x - 1) / gridDim.x;
+    const int i0 = g.off + blockIdx.x * chunk, i1 = min(g.off + g.n, i0 + chunk);
+    const size_t slot = (((size_t)blockIdx.y * gridDim.x + blockIdx.x) * (BAMG_BLK / BAMG_WAVE) + wv) * nv;
+    for (int b = 0; b < nv; ++b) {
+        const double* vb = V + (size_t)b * N;
+        double s = 0;
+        for (int i = i0 + threadIdx.x; i < i1; i += BAMG_BLK) s += vb[i] * w[i];
+        s = wave_sum(s);
+        if (lane == 0) part[slot + b] = s;
+    }
+}
+
+// h[c*HS + b] = sum of the partials; hacc[c*HAS + b] += h.  Block (b, c).
+__global__ void k_seg_mdot_final(int nparts, int nv, const int* __restrict__ act, const double* __restrict__ part,
+                                 double* __restrict__ h, int HS, double* __restrict__ hacc, int HAS) {
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    const int b = blockIdx.x, c = blockIdx.y;
+    if (!act[c]) return;
+    double s = 0;
+    for (int j = threadIdx.x; j < nparts; j += BAMG_BLK) s += part[((size_t)c * nparts + j) * nv + b];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) {
+        h[(size_t)c * HS + b] = s;
+        hacc[(size_t)c * HAS + b] += s;
+    }
+}
+
+// w -= sum_b h_b V_b on the rows of active chains.
+__global__ void k_seg_vupdate(int N, const ChainGeo* __restrict__ geo, int nch, int nv, const int* __restrict__ act,
+                              const double* __restrict__ V, const double* __restrict__ h, int HS,
+                              double* __restrict__ w) {
+    int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (i >= N) return;
+    const int c = find_chain(geo, nch, i);
+    if (!act[c]) return;
+    const double* hc = h + (size_t)c * HS;
+    double s = w[i];
+    for (int b = 0; b < nv; ++b) s -= hc[b] * V[(size_t)b * N + i];
+    w[i] = s;
+}
+
+// out_i = a_i * num_c / den_c (den_c square-rooted when sqrt_den) on the
+// rows of chains with act[c] (act null: all chains).
+__global__ void k_seg_scale(int N, const ChainGeo* __restrict__ geo, int nch, const int* __restrict__ act,
+                            const double* __restrict__ a, const double* __restrict__ num, const double* __restrict__ den,
+                            int stride, int sqrt_den, double* __restrict__ out) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i >= N) return;
+    const int c = find_chain(geo, nch, i);
+    if (act && !act[c]) return;
+    double d = den ? den[(size_t)c * stride] : 1.0;
+    if (sqrt_den) d = sqrt(d);
+    const double s = (num ? num[(size_t)c * stride] : 1.0) / d;
+    out[i] = a[i] * s;
+}
+
+// Givens step j for every active chain (one thread each); est[c] = |g_{j+1}|.
+__global__ void k_seg_givens(int nch, int j, int ld, const int* __restrict__ act, double* __restrict__ Hall, int HS,
+                             const double* __restrict__ hnew2, int hstride, double* __restrict__ csall,
+                             double* __restrict__ snall, double* __restrict__ gall, int GS, double* __restrict__ est) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nch || !act[c]) return;
+    double* col = Hall + (size_t)c * HS + (size_t)j * ld;
+    double* cs = csall + (size_t)c * GS;
+    double* sn = snall + (size_t)c * GS;
+    double* g = gall + (size_t)c * GS;
+    col[j + 1] = sqrt(hnew2[(size_t)c * hstride]);
+    for (int i = 0; i < j; ++i) {
+        double a = col[i], b = col[i + 1];
+        col[i] = cs[i] * a + sn[i] * b;
+        col[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    double a = col[j], b = col[j + 1];
+    double r = sqrt(a * a + b * b);
+    double cc = r > 0 ? a / r : 1.0, s = r > 0 ? b / r : 0.0;
+    cs[j] = cc; sn[j] = s;
+    col[j] = r; col[j + 1] = 0.0;
+    g[j + 1] = -s * g[j];
+    g[j] = cc * g[j];
+    est[c] = fabs(g[j + 1]);
+}
+
+// g = [beta_c, 0, ...] for every chain (beta2 per chain at stride).
+__global__ void k_seg_gmres_init(int nch, int m, const double* __restrict__ beta2, int stride, double* __restrict__ gall,
+                                 int GS) {
+    int c = blockIdx.x;
+    if (c >= nch) return;
+    for (int k = threadIdx.x; k <= m; k += blockDim.x) gall[(size_t)c * GS + k] = 0.0;
+    if (threadIdx.x == 0) gall[(size_t)c * GS] = sqrt(beta2[(size_t)c * stride]);
+}
+
+// Back substitution per chain with its own k = kd[c].
+__global__ void k_seg_gmres_y(int nch, int ld, const int* __restrict__ kd, const double* __restrict__ Hall, int HS,
+                              const double* __restrict__ gall, int GS, double* __restrict__ yall) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nch) return;
+    const int k = kd[c];
+    const double* H = Hall + (size_t)c * HS;
+    const double* g = gall + (size_t)c * GS;
+    double* y = yall + (size_t)c * GS;
+    for (int i = k - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int q = i + 1; q < k; ++q) s -= H[(size_t)q * ld + i] * y[q];
+        y[i] = s / H[(size_t)i * ld + i];
+    }
+}
+
+// x += sum_{j < kd[c]} y_cj Z_j.
+__global__ void k_seg_xupdate(int N, const ChainGeo* __restrict__ geo, int nch, const int* __restrict__ kd,
+                              const double* __restrict__ Z, const double* __restrict__ yall, int GS,
+                              double* __restrict__ x) {
+    int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (i >= N) return;
+    const int c = find_chain(geo, nch, i);
+    const int k = kd[c];
+    const double* y = yall + (size_t)c * GS;
+    double s = x[i];
+    for (int j = 0; j < k; ++j) s += y[j] * Z[(size_t)j * N + i];
+    x[i] = s;
+}
+
+// Gather / scatter between the caller's chain order and the internal one:
+// out[dst_off[c] + i] = in[src_off[c] + i] for i < len[c] (block y = chain).
+__global__ void k_seg_permute(const int* __restrict__ src_off, const int* __restrict__ dst_off,
+                              const int* __restrict__ len, const double* __restrict__ in, double* __restrict__ out) {
+    const int c = blockIdx.y;
+    for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < len[c]; i += gridDim.x * BAMG_BLK)
+        out[dst_off[c] + i] = in[src_off[c] + i];
+}
+
+// Reordered input CSR: rows of chain c move from src to dst offset; columns
+// shift with them.  Pass 1 copies row lengths, pass 2 (after a scan) the
+// entries.
+__global__ void k_seg_csr_len(int nch, const int* __restrict__ src_off, const int* __restrict__ dst_off,
+                              const int* __restrict__ len, const int* __restrict__ rp, int* __restrict__ cnt) {
+    const int c = blockIdx.y;
+    for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < len[c]; i += gridDim.x * BAMG_BLK)
+        cnt[dst_off[c] + i] = rp[src_off[c] + i + 1] - rp[src_off[c] + i];
+}
+
+__global__ void k_seg_csr_fill(const int* __restrict__ src_off, const int* __restrict__ dst_off,
+                               const int* __restrict__ len, const int* __restrict__ rp, const int* __restrict__ ci,
+                               const double* __restrict__ v, const int* __restrict__ nrp, int* __restrict__ nci,
+                               double* __restrict__ nv) {
+    const int c = blockIdx.y;
+    const int shift = dst_off[c] - src_off[c];
+    for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < len[c]; i += gridDim.x * BAMG_BLK) {
+        const int si = src_off[c] + i, di = dst_off[c] + i;
+        int q = nrp[di];
+        for (int p = rp[si]; p < rp[si + 1]; ++p, ++q) {
+            nci[q] = ci[p] + shift;
+            nv[q] = v[p];
+        }
+    }
+}
+
+// e = 0 (a fill kernel, so that a captured cycle holds no memset node).
+template <typename T>
+__global__ void k_fill_t(int n, T* __restrict__ e) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i < n) e[i] = (T)0;
+}

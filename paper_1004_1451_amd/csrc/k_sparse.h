@@ -39,23 +39,27 @@ __device__ __forceinline__ int grid_delta(int a1, int a2, int m, int periodic) {
 // diagonal is inserted).  Column sums accumulate with atomics: the check is a
 // tolerance test, so the summation order does not matter.
 __global__ void k_check_a(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                          const double* __restrict__ v, GridDev g, int nnz,
+                          const double* __restrict__ v, const ChainGeo* __restrict__ geo, int nch, int nnz,
                           double* __restrict__ colsum, int* __restrict__ cnt, int* __restrict__ err) {
     int i = blockIdx.x * BAMG_BLK + threadIdx.x;
     if (i >= n) return;
     int p0 = rp[i], p1 = rp[i + 1];
     int e = 0;
     if (p0 < 0 || p1 < p0 || p1 > nnz) { atomicOr(err, ERR_RANGE); cnt[i] = 1; return; }
-    int ia = (int)g.dy.div((uint32_t)i), ib = i - ia * g.ny;
+    const ChainGeo g = geo[find_chain(geo, nch, i)];
+    const int li = i - g.off;
+    int ia = (int)g.dy.div((uint32_t)li), ib = li - ia * g.ny;
     bool has_diag = false;
     int prev = -1;
     for (int p = p0; p < p1; ++p) {
         int j = ci[p];
         double a = v[p];
-        if (j < 0 || j >= n || j <= prev) { e |= ERR_RANGE; break; }
+        // columns stay inside the chain's own block (block-diagonal system)
+        if (j < g.off || j >= g.off + g.n || j <= prev) { e |= ERR_RANGE; break; }
         prev = j;
         if (!(a >= 0.0) || !(a <= 1.0 + 1e-12)) e |= ERR_NEG;
-        int ja = (int)g.dy.div((uint32_t)j), jb = j - ja * g.ny;
+        int lj = j - g.off;
+        int ja = (int)g.dy.div((uint32_t)lj), jb = lj - ja * g.ny;
         int da = grid_delta(ia, ja, g.nx, g.periodic), db = grid_delta(ib, jb, g.ny, g.periodic);
         if (da < -1 || da > 1 || db < -1 || db > 1) e |= ERR_WIDE;
         if (j == i) has_diag = true;
@@ -63,6 +67,15 @@ __global__ void k_check_a(int n, const int* __restrict__ rp, const int* __restri
     }
     if (e) atomicOr(err, e);
     cnt[i] = (p1 - p0) + (has_diag ? 0 : 1);
+}
+
+// row_ptr alone: 0 <= rp[i] <= rp[i+1] <= nnz (checked before any kernel
+// walks rows of a caller's CSR by index ranges).
+__global__ void k_check_rp(int n, const int* __restrict__ rp, int nnz, int* __restrict__ err) {
+    int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    const int p0 = rp[i], p1 = rp[i + 1];
+    if (p0 < 0 || p1 < p0 || p1 > nnz) atomicOr(err, ERR_RANGE);
 }
 
 __global__ void k_check_colsum(int n, const double* __restrict__ colsum, int* __restrict__ err) {
@@ -285,62 +298,79 @@ __global__ void k_interp(int n, int R, FastDiv divR, const int* __restrict__ pc,
 }
 
 // ---------------------------------------------------------------- TV weights
-// Stage 1: partial sums over a fixed partition of rows of (B x_k)_i^2 and
-// (x_k)_i^2 for every column k of X = [U | V] (U: Ru columns, V: Rv columns).
-// blockDim = R * floor(256 / R) so that a thread keeps its column across the
-// grid-stride loop.  part: [gridDim][2R] doubles.
+// Stage 1, per chain (blockIdx.y) and fixed row chunk (blockIdx.x): partial
+// sums of (B x_k)_i^2 and (x_k)_i^2 for the chain's columns k of X = [U | V]
+// (U: Ru columns, ld Ru; V: nv_c columns, ld VS; V unused when use_v == 0),
+// eight columns per pass.  part: [chain][chunk][2 * WS].
+#define COL_CHUNK 8
 template <typename T, typename M>
-__global__ void k_colnorm_partial(int n, int Ru, int Rv, FastDiv divR, const int* __restrict__ rp,
-                                  const int* __restrict__ ci, const M* __restrict__ v,
-                                  const T* __restrict__ U, const T* __restrict__ V,
-                                  double* __restrict__ part) {
-    __shared__ double shr[BAMG_BLK], shx[BAMG_BLK];
-    const int R = Ru + Rv;
-    const long long total = (long long)n * R;
-    const int stride = gridDim.x * blockDim.x;
-    double sr = 0, sx = 0;
-    int k = -1;
-    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
-        int i = (int)divR.div((uint32_t)t);
-        k = (int)(t - (long long)i * R);
-        const T* Xp = k < Ru ? U : V;
-        int ld = k < Ru ? Ru : Rv, kk = k < Ru ? k : k - Ru;
-        double acc = 0;
-        for (int p = rp[i]; p < rp[i + 1]; ++p) acc += (double)v[p] * (double)Xp[(size_t)ci[p] * ld + kk];
-        double x = (double)Xp[(size_t)i * ld + kk];
-        sr += acc * acc;
-        sx += x * x;
-    }
-    shr[threadIdx.x] = sr;
-    shx[threadIdx.x] = sx;
-    __syncthreads();
-    if ((int)threadIdx.x < R) {
-        double a = 0, b = 0;
-        for (int j = threadIdx.x; j < (int)blockDim.x; j += R) { a += shr[j]; b += shx[j]; }
-        // thread c reduces column (blockIdx.x*blockDim.x + c) % R
-        int col = (int)(((long long)blockIdx.x * blockDim.x + threadIdx.x) % R);
-        part[(size_t)blockIdx.x * 2 * R + col] = a;
-        part[(size_t)blockIdx.x * 2 * R + R + col] = b;
+__global__ void __launch_bounds__(BAMG_BLK)
+k_colnorm_partial(const ChainGeo* __restrict__ geo, int Ru, int use_v, const int* __restrict__ nvc, int VS,
+                  const int* __restrict__ rp, const int* __restrict__ ci, const M* __restrict__ v,
+                  const T* __restrict__ U, const T* __restrict__ V, int WS, double* __restrict__ part) {
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    const int c = blockIdx.y;
+    const ChainGeo g = geo[c];
+    const int R = Ru + (use_v ? nvc[c] : 0);
+    const int chunk = (g.n + gridDim.x - 1) / gridDim.x;
+    const int r0 = g.off + blockIdx.x * chunk, r1 = min(g.off + g.n, r0 + chunk);
+    double* out = part + ((size_t)c * gridDim.x + blockIdx.x) * 2 * WS;
+    for (int k0 = 0; k0 < R; k0 += COL_CHUNK) {
+        double sr[COL_CHUNK], sx[COL_CHUNK];
+#pragma unroll
+        for (int q = 0; q < COL_CHUNK; ++q) { sr[q] = 0; sx[q] = 0; }
+        for (int i = r0 + threadIdx.x; i < r1; i += BAMG_BLK) {
+            double acc[COL_CHUNK], xi[COL_CHUNK];
+#pragma unroll
+            for (int q = 0; q < COL_CHUNK; ++q) { acc[q] = 0; xi[q] = 0; }
+            for (int p = rp[i]; p < rp[i + 1]; ++p) {
+                const int j = ci[p];
+                const double b = (double)v[p];
+#pragma unroll
+                for (int q = 0; q < COL_CHUNK; ++q) {
+                    const int k = k0 + q;
+                    if (k < R) {
+                        const double x = k < Ru ? (double)U[(size_t)j * Ru + k] : (double)V[(size_t)j * VS + (k - Ru)];
+                        acc[q] += b * x;
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < COL_CHUNK; ++q) {
+                const int k = k0 + q;
+                if (k < R) xi[q] = k < Ru ? (double)U[(size_t)i * Ru + k] : (double)V[(size_t)i * VS + (k - Ru)];
+                sr[q] += acc[q] * acc[q];
+                sx[q] += xi[q] * xi[q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < COL_CHUNK; ++q) {
+            double a = block_sum(sr[q], sh);
+            double b = block_sum(sx[q], sh);
+            if (threadIdx.x == 0 && k0 + q < R) { out[k0 + q] = a; out[WS + k0 + q] = b; }
+        }
     }
 }
 
-// Stage 2: one block per column, fixed-order reduction over the partials;
+// Stage 2: block (chain c, column k) adds the chunk partials in order;
 // w_k = 1 / max(||B x_k||^2, (1e-14 ||x_k||)^2) (Section 3.2).
-__global__ void k_colnorm_final(int nparts, int R, const double* __restrict__ part, double* __restrict__ w,
-                                double* __restrict__ res2_out) {
+__global__ void k_colnorm_final(int nchunks, int Ru, int use_v, const int* __restrict__ nvc, int WS,
+                                const double* __restrict__ part, double* __restrict__ w) {
     __shared__ double sh[BAMG_BLK / BAMG_WAVE];
-    int k = blockIdx.x;
+    const int c = blockIdx.y, k = blockIdx.x;
+    const int R = Ru + (use_v ? nvc[c] : 0);
+    if (k >= R) return;
     double a = 0, b = 0;
-    for (int j = threadIdx.x; j < nparts; j += BAMG_BLK) {
-        a += part[(size_t)j * 2 * R + k];
-        b += part[(size_t)j * 2 * R + R + k];
+    for (int j = threadIdx.x; j < nchunks; j += BAMG_BLK) {
+        const double* p = part + ((size_t)c * nchunks + j) * 2 * WS;
+        a += p[k];
+        b += p[WS + k];
     }
     a = block_sum(a, sh);
     b = block_sum(b, sh);
     if (threadIdx.x == 0) {
         double den = a > 1e-28 * b ? a : 1e-28 * b;
-        w[k] = 1.0 / den;
-        if (res2_out) res2_out[k] = a;
+        w[(size_t)c * WS + k] = 1.0 / den;
     }
 }
 
@@ -397,14 +427,20 @@ __device__ __forceinline__ bool chol4(const double G[4][4], const double b[4], i
 // complement pivot).  Gram and solves in FP64 whatever the storage type.
 template <typename T, typename MP>
 __global__ void __launch_bounds__(BAMG_BLK)
-k_ls_fit(int n, GridDev g, int ncy, int Ru, int Rv, const T* __restrict__ U, const T* __restrict__ V,
-         const double* __restrict__ w, int caliber, int* __restrict__ pc, MP* __restrict__ pv,
-         T* __restrict__ inject, int* __restrict__ jmask) {
+k_ls_fit(int n, const ChainGeo* __restrict__ geo, int nch, int Ru, int use_v, const int* __restrict__ nvc,
+         int VS, const T* __restrict__ U, const T* __restrict__ V, const double* __restrict__ wall, int WS,
+         int caliber, int* __restrict__ pc, MP* __restrict__ pv, T* __restrict__ inject, int* __restrict__ jmask) {
     int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
     if (i >= n) return;
-    const int ia = (int)g.dy.div((uint32_t)i), ib = i - ia * g.ny;
+    const int ch = find_chain(geo, nch, i);
+    const ChainGeo g = geo[ch];
+    const int Rv = use_v ? nvc[ch] : 0;
+    const double* __restrict__ w = wall + (size_t)ch * WS;
+    const int ncy = g.ncy;
+    const int li = i - g.off;
+    const int ia = (int)g.dy.div((uint32_t)li), ib = li - ia * g.ny;
     if (((ia | ib) & 1) == 0) {
-        int I = (ia >> 1) * ncy + (ib >> 1);
+        int I = g.coff + (ia >> 1) * ncy + (ib >> 1);
         pc[(size_t)i * 4] = I; pv[(size_t)i * 4] = (MP)1;
 #pragma unroll
         for (int s = 1; s < 4; ++s) { pc[(size_t)i * 4 + s] = -1; pv[(size_t)i * 4 + s] = (MP)0; }
@@ -434,7 +470,7 @@ k_ls_fit(int n, GridDev g, int ncy, int Ru, int Rv, const T* __restrict__ U, con
             // at most 4 coarse points in the box; ns < 4 always holds here
 #pragma unroll
             for (int s = 0; s < 4; ++s)
-                if (s == ns) { sf[s] = na * g.ny + nb; sc[s] = (na >> 1) * ncy + (nb >> 1); }
+                if (s == ns) { sf[s] = g.off + na * g.ny + nb; sc[s] = g.coff + (na >> 1) * ncy + (nb >> 1); }
             ++ns;
         }
     int valid = (1 << ns) - 1;
@@ -449,10 +485,11 @@ k_ls_fit(int n, GridDev g, int ncy, int Ru, int Rv, const T* __restrict__ U, con
     // U columns, then V columns (test vectors in a fixed order k = 0..R-1)
     for (int part = 0; part < 2; ++part) {
         const T* Xp = part == 0 ? U : V;
-        const int ld = part == 0 ? Ru : Rv;
+        const int ld = part == 0 ? Ru : VS;
+        const int nk = part == 0 ? Ru : Rv;
         const double* wp = w + (part == 0 ? 0 : Ru);
 #pragma unroll 2
-        for (int kk = 0; kk < ld; ++kk) {
+        for (int kk = 0; kk < nk; ++kk) {
             double wk = wp[kk];
             double xi = (double)Xp[(size_t)i * ld + kk];
             double xs[4];
@@ -539,11 +576,15 @@ k_ls_fit(int n, GridDev g, int ncy, int Ru, int Rv, const T* __restrict__ U, con
 // I in J_i.  Such i lie in the 3x3 fine box around I's fine position; they
 // are written in ascending fine index.
 template <typename MQ>
-__global__ void k_build_q(int nc, GridDev g, FastDiv dcy, int ncy, const int* __restrict__ pc,
-                          int* __restrict__ qc, MQ* __restrict__ qv) {
+__global__ void k_build_q(int nc, const ChainGeo* __restrict__ geoc, const ChainGeo* __restrict__ geof, int nch,
+                          const int* __restrict__ pc, int* __restrict__ qc, MQ* __restrict__ qv) {
     int I = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
     if (I >= nc) return;
-    int A = (int)dcy.div((uint32_t)I), Bq = I - A * ncy;
+    const int ch = find_chain(geoc, nch, I);
+    const ChainGeo gc = geoc[ch];
+    const ChainGeo g = geof[ch];
+    const int lI = I - gc.off;
+    int A = (int)gc.dy.div((uint32_t)lI), Bq = lI - A * gc.ny;
     int fa = 2 * A, fb = 2 * Bq;
     int fi[9];
     double fv[9];
@@ -558,7 +599,7 @@ __global__ void k_build_q(int nc, GridDev g, FastDiv dcy, int ncy, const int* __
         } else if (na < 0 || na >= g.nx || nb < 0 || nb >= g.ny) {
             continue;
         }
-        int i = na * g.ny + nb;
+        int i = g.off + na * g.ny + nb;
         int c = 0;
         bool hit = false;
 #pragma unroll
@@ -587,6 +628,7 @@ __global__ void k_build_q(int nc, GridDev g, FastDiv dcy, int ncy, const int* __
 // ---------------------------------------------------------------- Galerkin
 // Slot (0..8) of coarse column J in the 3x3 coarse box around coarse row I.
 __device__ __forceinline__ int box_slot(int I_a, int I_b, int J, const FastDiv& dcy, int ncx, int ncy, int periodic) {
+    // J: coarse column relative to the chain's first coarse row
     int Ja = (int)dcy.div((uint32_t)J), Jb = J - Ja * ncy;
     int da = grid_delta(I_a, Ja, ncx, periodic), db = grid_delta(I_b, Jb, ncy, periodic);
     return (da + 1) * 3 + (db + 1);
@@ -601,7 +643,7 @@ __device__ __forceinline__ int box_slot(int I_a, int I_b, int J, const FastDiv& 
 // i = qc[9I+s] (mask) and, with vals, tmp[u] = sum_j m_ij p_jJ (M-row order,
 // then P-row order) for J in box slot u.
 template <typename MV, bool VALS>
-__device__ __forceinline__ unsigned gal_slot(int I, int Ia, int Ib, int i, const FastDiv& dcy, int ncx, int ncy,
+__device__ __forceinline__ unsigned gal_slot(int coff, int Ia, int Ib, int i, const FastDiv& dcy, int ncx, int ncy,
                                              int periodic, const int* __restrict__ mrp, const int* __restrict__ mci,
                                              const MV* __restrict__ mv, const int* __restrict__ pc,
                                              const MV* __restrict__ pv, MV* tmp) {
@@ -620,7 +662,7 @@ __device__ __forceinline__ unsigned gal_slot(int I, int Ia, int Ib, int i, const
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             if (Js[t] < 0) continue;
-            int sl = box_slot(Ia, Ib, Js[t], dcy, ncx, ncy, periodic);
+            int sl = box_slot(Ia, Ib, Js[t] - coff, dcy, ncx, ncy, periodic);
             mask |= 1u << sl;
             if (VALS) {
                 MV c = m * ps[t];
@@ -636,7 +678,7 @@ __device__ __forceinline__ unsigned gal_slot(int I, int Ia, int Ib, int i, const
 // I (every coarse stencil lies in that box: Q, M and P each reach one grid
 // step).  cnt[I] = number of distinct columns.  M == identity when mrp is null.
 __global__ void __launch_bounds__(GAL_THREADS)
-k_galerkin_symbolic(int nc, FastDiv dcy, int ncx, int ncy, int periodic,
+k_galerkin_symbolic(int nc, const ChainGeo* __restrict__ geoc, int nch,
                     const int* __restrict__ qc, const int* __restrict__ mrp,
                     const int* __restrict__ mci, const int* __restrict__ pc,
                     int* __restrict__ cnt, unsigned short* __restrict__ mask_out) {
@@ -647,9 +689,11 @@ k_galerkin_symbolic(int nc, FastDiv dcy, int ncx, int ncy, int periodic,
     if (I < nc) {
         int i = qc[(size_t)I * 9 + s];
         if (i >= 0) {
-            int Ia = (int)dcy.div((uint32_t)I), Ib = I - Ia * ncy;
-            mask = gal_slot<float, false>(I, Ia, Ib, i, dcy, ncx, ncy, periodic, mrp, mci, (const float*)nullptr,
-                                          pc, (const float*)nullptr, nullptr);
+            const ChainGeo g = geoc[find_chain(geoc, nch, I)];
+            const int lI = I - g.off;
+            int Ia = (int)g.dy.div((uint32_t)lI), Ib = lI - Ia * g.ny;
+            mask = gal_slot<float, false>(g.off, Ia, Ib, i, g.dy, g.nx, g.ny, g.periodic, mrp, mci,
+                                          (const float*)nullptr, pc, (const float*)nullptr, nullptr);
         }
     }
     sm[threadIdx.x] = mask;
@@ -668,7 +712,7 @@ k_galerkin_symbolic(int nc, FastDiv dcy, int ncx, int ncy, int periodic,
 // column at crp[I].
 template <typename MV>
 __global__ void __launch_bounds__(GAL_THREADS)
-k_galerkin_numeric(int nc, FastDiv dcy, int ncx, int ncy, int periodic,
+k_galerkin_numeric(int nc, const ChainGeo* __restrict__ geoc, int nch,
                    const int* __restrict__ qc, const MV* __restrict__ qv,
                    const int* __restrict__ mrp, const int* __restrict__ mci, const MV* __restrict__ mv,
                    const int* __restrict__ pc, const MV* __restrict__ pv,
@@ -680,13 +724,16 @@ k_galerkin_numeric(int nc, FastDiv dcy, int ncx, int ncy, int periodic,
     MV tmp[9];
 #pragma unroll
     for (int u = 0; u < 9; ++u) tmp[u] = 0;
-    int Ia = 0, Ib = 0;
+    int Ia = 0, Ib = 0, ncx = 1, ncy = 1, periodic = 0, goff = 0;
     if (I < nc) {
-        Ia = (int)dcy.div((uint32_t)I); Ib = I - Ia * ncy;
+        const ChainGeo g = geoc[find_chain(geoc, nch, I)];
+        ncx = g.nx; ncy = g.ny; periodic = g.periodic; goff = g.off;
+        const int lI = I - g.off;
+        Ia = (int)g.dy.div((uint32_t)lI); Ib = lI - Ia * ncy;
         int i = qc[(size_t)I * 9 + s];
         if (i >= 0) {
             MV q = qv[(size_t)I * 9 + s];
-            gal_slot<MV, true>(I, Ia, Ib, i, dcy, ncx, ncy, periodic, mrp, mci, mv, pc, pv, tmp);
+            gal_slot<MV, true>(g.off, Ia, Ib, i, g.dy, ncx, ncy, periodic, mrp, mci, mv, pc, pv, tmp);
 #pragma unroll
             for (int u = 0; u < 9; ++u) tmp[u] = q * tmp[u];
         }
@@ -709,7 +756,7 @@ k_galerkin_numeric(int nc, FastDiv dcy, int ncx, int ncy, int periodic,
             a = a < 0 ? a + ncx : (a >= ncx ? a - ncx : a);
             b = b < 0 ? b + ncy : (b >= ncy ? b - ncy : b);
         }
-        col[w] = a * ncy + b;
+        col[w] = goff + a * ncy + b;
     }
     int rank = 0;
 #pragma unroll
@@ -726,28 +773,34 @@ k_galerkin_numeric(int nc, FastDiv dcy, int ncx, int ncy, int periodic,
 // null.  Column 0 (the null-vector approximation) has lam = 0.
 template <typename T, typename M>
 __global__ void __launch_bounds__(BAMG_BLK)
-k_eig_relax(int n, int R, const int* __restrict__ brp, const int* __restrict__ bci, const M* __restrict__ bv,
+k_eig_relax(int n, const ChainGeo* __restrict__ geo, int nch, int R, const int* __restrict__ nvc, int KV,
+            const int* __restrict__ brp, const int* __restrict__ bci, const M* __restrict__ bv,
             const int* __restrict__ trp, const int* __restrict__ tci, const M* __restrict__ tv,
-            const double* __restrict__ lam, const int* __restrict__ kind, double omega,
+            const double* __restrict__ lamall, const int* __restrict__ kindall, double omega,
             const T* __restrict__ X, T* __restrict__ Y) {
     int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
     if (i >= n) return;
+    // R: row stride of X / Y; the chain uses its first nvc columns
+    const int ch = find_chain(geo, nch, i);
+    const int nv = nvc[ch];
+    const double* __restrict__ lam = lamall + (size_t)ch * 2 * KV;
+    const int* __restrict__ kind = kindall + (size_t)ch * KV;
     double bx[10], tx[10], bd = 0, td = trp ? 0.0 : 1.0;
-    for (int c = 0; c < R; ++c) { bx[c] = 0; tx[c] = trp ? 0.0 : (double)X[(size_t)i * R + c]; }
+    for (int c = 0; c < nv; ++c) { bx[c] = 0; tx[c] = trp ? 0.0 : (double)X[(size_t)i * R + c]; }
     for (int p = brp[i]; p < brp[i + 1]; ++p) {
         int j = bci[p];
         double b = (double)bv[p];
         if (j == i) bd = b;
-        for (int c = 0; c < R; ++c) bx[c] += b * (double)X[(size_t)j * R + c];
+        for (int c = 0; c < nv; ++c) bx[c] += b * (double)X[(size_t)j * R + c];
     }
     if (trp)
         for (int p = trp[i]; p < trp[i + 1]; ++p) {
             int j = tci[p];
             double t = (double)tv[p];
             if (j == i) td = t;
-            for (int c = 0; c < R; ++c) tx[c] += t * (double)X[(size_t)j * R + c];
+            for (int c = 0; c < nv; ++c) tx[c] += t * (double)X[(size_t)j * R + c];
         }
-    for (int c = 0; c < R; ++c) {
+    for (int c = 0; c < nv; ++c) {
         int k = kind[c];
         double lr = lam[2 * c], li = lam[2 * c + 1];
         if (k == 0) {
@@ -768,20 +821,28 @@ k_eig_relax(int n, int R, const int* __restrict__ brp, const int* __restrict__ b
     }
 }
 
-// Rayleigh quotient partials for column pair/real column c: x^H B x and
-// x^H T x (re, im) -> part[block][entry][4].  ent_col: first column of entry e.
+// Rayleigh quotient partials, per chain (blockIdx.y) and fixed row chunk
+// (blockIdx.x): for entry e (first column ent_col[e]; a pair uses two) the
+// sums x^H B x and x^H T x (re, im) -> part[chain][chunk][entry][4].
 template <typename T, typename M>
-__global__ void k_rayleigh_partial(int n, int R, int nent, const int* __restrict__ ent_col,
-                                   const int* __restrict__ kind,
+__global__ void k_rayleigh_partial(const ChainGeo* __restrict__ geo, int R, int KV, const int* __restrict__ nentc,
+                                   const int* __restrict__ ent_colall, const int* __restrict__ kindall,
                                    const int* __restrict__ brp, const int* __restrict__ bci, const M* __restrict__ bv,
                                    const int* __restrict__ trp, const int* __restrict__ tci, const M* __restrict__ tv,
                                    const T* __restrict__ X, double* __restrict__ part) {
     __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    const int chn = blockIdx.y;
+    const ChainGeo g = geo[chn];
+    const int nent = nentc[chn];
+    const int* ent_col = ent_colall + (size_t)chn * KV;
+    const int* kind = kindall + (size_t)chn * KV;
+    const int chunk = (g.n + gridDim.x - 1) / gridDim.x;
+    const int r0 = g.off + blockIdx.x * chunk, r1 = min(g.off + g.n, r0 + chunk);
     for (int e = 0; e < nent; ++e) {
         int c = ent_col[e];
         bool pair = kind[c] == 1;
         double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-        for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < n; i += gridDim.x * BAMG_BLK) {
+        for (int i = r0 + threadIdx.x; i < r1; i += BAMG_BLK) {
             double xr = (double)X[(size_t)i * R + c], xi = pair ? (double)X[(size_t)i * R + c + 1] : 0.0;
             double br = 0, bi = 0, tr = 0, ti = 0;
             for (int p = brp[i]; p < brp[i + 1]; ++p) {
@@ -806,23 +867,28 @@ __global__ void k_rayleigh_partial(int n, int R, int nent, const int* __restrict
         }
         s0 = block_sum(s0, sh); s1 = block_sum(s1, sh); s2 = block_sum(s2, sh); s3 = block_sum(s3, sh);
         if (threadIdx.x == 0) {
-            double* o = part + ((size_t)blockIdx.x * nent + e) * 4;
+            double* o = part + (((size_t)chn * gridDim.x + blockIdx.x) * KV + e) * 4;
             o[0] = s0; o[1] = s1; o[2] = s2; o[3] = s3;
         }
     }
 }
 
 // lam_e = (x^H B x) / (x^H T x) for every entry except the null vector
-// (entry 0 keeps lam = 0); real columns keep a real lam.
-__global__ void k_rayleigh_final(int nparts, int nent, const int* __restrict__ ent_col, const int* __restrict__ kind,
-                                 const double* __restrict__ part, double* __restrict__ lam) {
+// (entry 0 keeps lam = 0); real columns keep a real lam.  Block (e, chain).
+__global__ void k_rayleigh_final(int nchunks, int KV, const int* __restrict__ nentc, const int* __restrict__ ent_colall,
+                                 const int* __restrict__ kindall, const double* __restrict__ part,
+                                 double* __restrict__ lamall) {
     __shared__ double sh[BAMG_BLK / BAMG_WAVE];
-    int e = blockIdx.x;
+    const int e = blockIdx.x, chn = blockIdx.y;
+    if (e >= nentc[chn] || e == 0) return;
     double s[4] = {0, 0, 0, 0};
-    for (int j = threadIdx.x; j < nparts; j += BAMG_BLK)
-        for (int q = 0; q < 4; ++q) s[q] += part[((size_t)j * nent + e) * 4 + q];
+    for (int j = threadIdx.x; j < nchunks; j += BAMG_BLK)
+        for (int q = 0; q < 4; ++q) s[q] += part[(((size_t)chn * nchunks + j) * KV + e) * 4 + q];
     for (int q = 0; q < 4; ++q) s[q] = block_sum(s[q], sh);
-    if (threadIdx.x == 0 && e > 0) {
+    if (threadIdx.x == 0) {
+        const int* ent_col = ent_colall + (size_t)chn * KV;
+        const int* kind = kindall + (size_t)chn * KV;
+        double* lam = lamall + (size_t)chn * 2 * KV;
         int c = ent_col[e];
         double den = s[2] * s[2] + s[3] * s[3];
         double lr = (s[0] * s[2] + s[1] * s[3]) / den, li = (s[1] * s[2] - s[0] * s[3]) / den;
@@ -839,9 +905,14 @@ __global__ void k_cast(long long n, const A* __restrict__ a, B* __restrict__ b) 
     if (i < n) b[i] = (B)a[i];
 }
 
-// Initial test vectors U[i*r + k] = u(seed, stream 1, i*r + k).
+// Initial test vectors: entry (i, k) of a chain's block is u(seed, stream 1,
+// i_local * r + k), the same numbers a single-chain setup draws.
 template <typename T>
-__global__ void k_tv_init(long long total, uint64_t seed, T* __restrict__ U) {
+__global__ void k_tv_init(long long total, int r, FastDiv divr, const ChainGeo* __restrict__ geo, int nch,
+                          uint64_t seed, T* __restrict__ U) {
     long long t = (long long)blockIdx.x * BAMG_BLK + threadIdx.x;
-    if (t < total) U[t] = (T)splitmix_u01(seed, 1ull, (uint64_t)t);
+    if (t >= total) return;
+    int i = (int)divr.div((uint32_t)t), k = (int)(t - (long long)i * r);
+    const ChainGeo g = geo[find_chain(geo, nch, i)];
+    U[t] = (T)splitmix_u01(seed, 1ull, (uint64_t)(i - g.off) * r + k);
 }
