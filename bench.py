@@ -69,96 +69,166 @@ def cpu_baseline(args):
             "converged": bool(info.converged)}
 
 
+def cpu_baseline_batch(chains, args, budget_s=15.0):
+    """The oracle on a bounded sample of the batch: chains in the batch's own
+    order until about budget_s seconds of single-thread work, scaled to the
+    whole batch by the ratio of state counts."""
+    from threadpoolctl import threadpool_limits
+    from oracle import bamg_oracle as O
+    done_n, dt, k, conv = 0, 0.0, 0, True
+    with threadpool_limits(limits=1):
+        for ch in chains:
+            if dt > budget_s:
+                break
+            t0 = time.perf_counter()
+            _, info, _ = O.stationary(ch.to_scipy(), O.Grid(ch.nx, ch.ny, ch.periodic), args.r,
+                                      O.Options(levels=0, coarse_max=1024), tol=args.tol, max_cycles=200)
+            dt += time.perf_counter() - t0
+            done_n += ch.n
+            k += 1
+            conv &= bool(info.converged)
+    total = sum(ch.n for ch in chains)
+    scale = total / done_n
+    return {"value": dt * scale, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle setup+solve on the first {k} of {len(chains)} chains ({done_n:,} of {total:,} states) "
+                      f"took {dt:.2f} s on 1 thread; scaled by n ratio {scale:.1f}",
+            "converged": conv}
+
+
+def _roofline(stats, traffic):
+    sweep_ms = sum(s.sweep_ms for s in stats) / max(1, sum(s.sweep_launches for s in stats))
+    sweep_bytes = stats[-1].sweep_bytes
+    achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9
+    return sweep_ms, {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                      "kernel": "k_sweep (level-0 test-vector sweep)",
+                      "bytes_per_launch": int(sweep_bytes), "mean_launch_us": round(sweep_ms * 1e3, 2)}
+
+
+def _kernel_detail(stats):
+    gal_ms = sum(s.galerkin_ms for s in stats) / max(1, sum(s.galerkin_launches for s in stats))
+    ls_ms = sum(s.lsfit_ms for s in stats) / max(1, sum(s.lsfit_launches for s in stats))
+    return {
+        "setup_ms": round(float(np.mean([s.t_setup_ms for s in stats])), 3),
+        "solve_ms": round(float(np.mean([s.t_solve_ms for s in stats])), 3),
+        "op_complexity": round(stats[-1].op_complexity, 4),
+        "galerkin_numeric_us": round(gal_ms * 1e3, 2),
+        "galerkin_GBps": round(stats[-1].galerkin_bytes / (gal_ms * 1e-3) / 1e9, 1) if gal_ms > 0 else None,
+        "lsfit_us": round(ls_ms * 1e3, 2),
+        "lsfit_GBps": round(stats[-1].lsfit_bytes / (ls_ms * 1e-3) / 1e9, 1) if ls_ms > 0 else None,
+        "coarsest_min_pivot": stats[-1].coarsest_min_pivot,
+    }
+
+
+def _timed(step, args):
+    import torch
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    res = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res.append(step())
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / args.steps, res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["tandem", "batch64"], default="tandem",
+                    help="tandem: one tandem queue (default N=2047, n=4.2M); batch64: 64 mixed chains in one handle")
     ap.add_argument("--N", type=int, default=2047, help="tandem queue capacity (side N+1)")
     ap.add_argument("--levels", type=int, default=6)
     ap.add_argument("--r", type=int, default=12)
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
+                    help="default: fp64 for tandem, mixed for batch64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is described "
               f"in DESIGN.md and not built", file=sys.stderr)
         sys.exit(2)
+    if args.precision is None:
+        args.precision = "fp64" if args.workload == "tandem" else "mixed"
 
     import torch
     from paper_1004_1451_amd import bamg as B
     from paper_1004_1451_amd import chains as C
 
-    ch = C.tandem_queue(args.N)
-    rp, ci, v = B.device_csr(ch)
-    x = torch.empty(ch.n, dtype=torch.float64, device="cuda")
     prec = B.FP64 if args.precision == "fp64" else B.MIXED
-    opts = B.default_options(levels=args.levels, precision=prec, profile=1)
-
-    def step():
-        h = B.Hierarchy(ch.n, rp, ci, v, (ch.nx, ch.ny, 0), args.r, opts)
-        info = h.solve(x, args.tol, 200)
-        st = h.stats()
-        h.close()
-        return info, st
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    infos, stats = [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        info, st = step()
-        infos.append(info)
-        stats.append(st)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    sec = dt / args.steps
-
-    sweep_ms = sum(s.sweep_ms for s in stats) / max(1, sum(s.sweep_launches for s in stats))
-    sweep_bytes = stats[-1].sweep_bytes
-    achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9
-    gal_ms = sum(s.galerkin_ms for s in stats) / max(1, sum(s.galerkin_launches for s in stats))
-    ls_ms = sum(s.lsfit_ms for s in stats) / max(1, sum(s.lsfit_launches for s in stats))
     traffic = _traffic_from_profiles("k_sweep")
-    out = {
-        "metric": "setup+solve seconds to ||Bx||_1/||x||_1<=1e-10 at n=4.2M; sweep HBM GB/s",
-        "value": round(sec, 6),
-        "unit": "s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(sec * 1e3, 3),
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if prec == B.FP64 else "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": f"tandem queue N={args.N} (n={ch.n:,}), rates 11/31,10/31,10/31, r={args.r}, "
-                               f"{args.levels} levels, tol {args.tol:g}",
-                   "precision": args.precision},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                     "kernel": "k_sweep (level-0 test-vector sweep, R=%d)" % args.r,
-                     "bytes_per_launch": int(sweep_bytes), "mean_launch_us": round(sweep_ms * 1e3, 2)},
-        "detail": {
-            "setup_ms": round(float(np.mean([s.t_setup_ms for s in stats])), 3),
-            "solve_ms": round(float(np.mean([s.t_solve_ms for s in stats])), 3),
-            "cycles": [i.cycles for i in infos],
-            "history": [float("%.3e" % v) for v in list(infos[-1].history)[: infos[-1].history_len]],
-            "residual_l1": max(i.residual_l1 for i in infos),
-            "converged": all(i.converged for i in infos),
-            "op_complexity": round(stats[-1].op_complexity, 4),
-            "galerkin_numeric_us": round(gal_ms * 1e3, 2),
-            "galerkin_GBps": round(stats[-1].galerkin_bytes / (gal_ms * 1e-3) / 1e9, 1) if gal_ms > 0 else None,
-            "lsfit_us": round(ls_ms * 1e3, 2),
-            "lsfit_GBps": round(stats[-1].lsfit_bytes / (ls_ms * 1e-3) / 1e9, 1) if ls_ms > 0 else None,
-            "coarsest_min_pivot": stats[-1].coarsest_min_pivot,
-        },
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args)
+    if args.workload == "tandem":
+        ch = C.tandem_queue(args.N)
+        rp, ci, v = B.device_csr(ch)
+        x = torch.empty(ch.n, dtype=torch.float64, device="cuda")
+        opts = B.default_options(levels=args.levels, precision=prec, profile=1)
+
+        def step():
+            h = B.Hierarchy(ch.n, rp, ci, v, (ch.nx, ch.ny, 0), args.r, opts)
+            info = h.solve(x, args.tol, 200)
+            st = h.stats()
+            h.close()
+            return info, st
+
+        sec, res = _timed(step, args)
+        infos = [a for a, _ in res]
+        stats = [b for _, b in res]
+        sweep_ms, roof = _roofline(stats, traffic)
+        roof["kernel"] += ", R=%d" % args.r
+        detail = _kernel_detail(stats)
+        detail.update({"cycles": [i.cycles for i in infos],
+                       "history": [float("%.3e" % v) for v in list(infos[-1].history)[: infos[-1].history_len]],
+                       "residual_l1": max(i.residual_l1 for i in infos),
+                       "converged": all(i.converged for i in infos)})
+        out = {
+            "metric": "setup+solve seconds to ||Bx||_1/||x||_1<=1e-10 at n=4.2M; sweep HBM GB/s",
+            "value": round(sec, 6), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(sec * 1e3, 3), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if prec == B.FP64 else "f32+f64", "data": "synthetic",
+            "config": {"workload": f"tandem queue N={args.N} (n={ch.n:,}), rates 11/31,10/31,10/31, r={args.r}, "
+                                   f"{args.levels} levels, tol {args.tol:g}", "precision": args.precision},
+            "roofline": roof, "detail": detail,
+        }
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(args)
+    else:
+        chains = C.batch_mix(64)
+        db = B.DeviceBatch(chains)
+        x = torch.empty(db.n, dtype=torch.float64, device="cuda")
+        opts = B.default_options(levels=0, coarse_max=1024, precision=prec, profile=1)
+
+        def step():
+            h = B.BatchedHierarchy(db, args.r, opts)
+            info, status, resid = h.solve_batched(x, args.tol, 200)
+            st = h.stats()
+            h.close()
+            return info, status, resid, st
+
+        sec, res = _timed(step, args)
+        stats = [r[3] for r in res]
+        sweep_ms, roof = _roofline(stats, None)
+        roof["kernel"] += ", R=%d, all 64 chains" % args.r
+        detail = _kernel_detail(stats)
+        detail.update({"chains_per_s": round(64 / sec, 2), "cycles": [r[0].cycles for r in res],
+                       "worst_chain_residual": float(max(r[2].max() for r in res)),
+                       "all_chains_converged": bool(all(r[1].all() for r in res)),
+                       "levels_max": stats[-1].n_levels})
+        out = {
+            "metric": "batched setup+solve seconds, 64 chains, every chain to ||Bx||_1/||x||_1<=1e-10",
+            "value": round(sec, 6), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(sec * 1e3, 3), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if prec == B.FP64 else "f32+f64", "data": "synthetic",
+            "config": {"workload": f"64 chains (tandem N in [31,511] jittered, periodic lattices side in [32,512]), "
+                                   f"n={db.n:,}, r={args.r}, coarsen to <=1024, tol {args.tol:g}",
+                       "precision": args.precision},
+            "roofline": roof, "detail": detail,
+        }
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline_batch(chains, args)
     print(json.dumps(out))
 
 

@@ -94,6 +94,9 @@ typedef struct {
     int32_t stop_after;  /* 0: full setup; 1: after the first down-leg;
                             2: after the coarsest eigensolve; 3: after the
                             up-leg (inspection only)                          */
+    int32_t cycle_mode;  /* 0: decide on the first cycle (graph when the cycle
+                            is launch-bound); 1: eager launches; 2: HIP graph
+                            of one cycle, captured once and replayed          */
 } bamg_options;
 
 typedef struct {
@@ -117,6 +120,9 @@ typedef struct {
     double sweep_ms, galerkin_ms, lsfit_ms;
     int32_t sweep_launches, galerkin_launches, lsfit_launches;
     int64_t sweep_bytes, galerkin_bytes, lsfit_bytes; /* algorithmic bytes per launch */
+    int32_t cycle_graph;    /* 1: cycles replay a captured graph              */
+    double cycle_host_us, cycle_gpu_us; /* first cycle (cycle_mode 0): host launch
+                                           time and GPU time                 */
 } bamg_stats;
 
 typedef struct {
@@ -204,7 +210,9 @@ int bamg_solve_batched(bamg_handle h, double* x, double tol, int32_t max_cycles,
                        uint32_t flags, int32_t* chain_status,
                        double* chain_residual, bamg_solve_info* info);
 
-/* Release everything the handle owns.  NULL is allowed. */
+/* Release everything the handle owns.  NULL is allowed.  Device memory goes
+   back to the device's default stream-ordered pool, which the library sets to
+   keep freed memory for reuse (hipMemPoolAttrReleaseThreshold = max). */
 int bamg_free(bamg_handle h);
 
 /* Message of the last failing call on this thread ("" if none). */

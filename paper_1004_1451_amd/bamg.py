@@ -49,7 +49,7 @@ class Options(C.Structure):
                 ("caliber", C.c_int32), ("n_eig", C.c_int32), ("arnoldi_m", C.c_int32),
                 ("gmres_m", C.c_int32), ("precision", C.c_int32), ("interp", C.c_int32),
                 ("mlp_weights", C.c_void_p), ("seed", C.c_uint64), ("mem_budget", C.c_size_t),
-                ("profile", C.c_int32), ("stop_after", C.c_int32)]
+                ("profile", C.c_int32), ("stop_after", C.c_int32), ("cycle_mode", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -63,7 +63,8 @@ class Stats(C.Structure):
                 ("coarsest_min_pivot", C.c_double), ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double),
                 ("sweep_ms", C.c_double), ("galerkin_ms", C.c_double), ("lsfit_ms", C.c_double),
                 ("sweep_launches", C.c_int32), ("galerkin_launches", C.c_int32), ("lsfit_launches", C.c_int32),
-                ("sweep_bytes", C.c_int64), ("galerkin_bytes", C.c_int64), ("lsfit_bytes", C.c_int64)]
+                ("sweep_bytes", C.c_int64), ("galerkin_bytes", C.c_int64), ("lsfit_bytes", C.c_int64),
+                ("cycle_graph", C.c_int32), ("cycle_host_us", C.c_double), ("cycle_gpu_us", C.c_double)]
 
 
 class LevelInfo(C.Structure):
@@ -221,25 +222,37 @@ def concat_chains(chains):
     return off, rp, ci, v, grids
 
 
-class BatchedHierarchy(Hierarchy):
-    """Owns a bamg_handle made by bamg_setup_batched (several chains, one handle)."""
+class DeviceBatch:
+    """Concatenated chains resident on the device (inputs of bamg_setup_batched)."""
 
-    def __init__(self, chains, r, options: Options | None = None, stream=None):
+    def __init__(self, chains, device="cuda"):
         import torch
-        lib = load()
-        self._h = C.c_void_p()
         off, rp, ci, v, grids = concat_chains(chains)
         self.nchains = len(chains)
         self.offsets = off
         self.n = int(off[-1])
-        drp = torch.as_tensor(rp, device="cuda")
-        dci = torch.as_tensor(ci, device="cuda")
-        dv = torch.as_tensor(v, device="cuda")
-        garr = (Grid * self.nchains)(*[Grid(int(a), int(b), int(c)) for a, b, c in grids])
+        self.row_ptr = torch.as_tensor(rp, device=device)
+        self.col_idx = torch.as_tensor(ci, device=device)
+        self.val = torch.as_tensor(v, device=device)
+        self.grids = (Grid * self.nchains)(*[Grid(int(a), int(b), int(c)) for a, b, c in grids])
+
+
+class BatchedHierarchy(Hierarchy):
+    """Owns a bamg_handle made by bamg_setup_batched (several chains, one handle).
+    `chains` is a list of Chain objects or a DeviceBatch already on the device."""
+
+    def __init__(self, chains, r, options: Options | None = None, stream=None):
+        lib = load()
+        self._h = C.c_void_p()
+        db = chains if isinstance(chains, DeviceBatch) else DeviceBatch(chains)
+        self.nchains = db.nchains
+        self.offsets = db.offsets
+        self.n = db.n
         opts = options if options is not None else default_options()
-        _check(lib.bamg_setup_batched(self.nchains, off.ctypes.data_as(C.c_void_p), C.c_void_p(drp.data_ptr()),
-                                      C.c_void_p(dci.data_ptr()), C.c_void_p(dv.data_ptr()), garr, int(r),
-                                      C.byref(opts), _stream_ptr(stream), C.byref(self._h)))
+        _check(lib.bamg_setup_batched(self.nchains, db.offsets.ctypes.data_as(C.c_void_p),
+                                      C.c_void_p(db.row_ptr.data_ptr()), C.c_void_p(db.col_idx.data_ptr()),
+                                      C.c_void_p(db.val.data_ptr()), db.grids, int(r), C.byref(opts),
+                                      _stream_ptr(stream), C.byref(self._h)))
 
     def solve_batched(self, x, tol=1e-10, max_cycles=200, use_guess=False):
         """Returns (info, per-chain status int32 array, per-chain residual array)."""

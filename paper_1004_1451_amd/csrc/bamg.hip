@@ -63,8 +63,10 @@ struct BamgError : std::runtime_error {
     } while (0)
 
 inline int nblk(long long n) { return (int)std::max<long long>(1, (n + BAMG_BLK - 1) / BAMG_BLK); }
-constexpr int SEG_PARTS = 64;     // fixed chunks per chain of the per-chain reductions
-constexpr int MDOT_PARTS = 64;    // fixed chunks per chain of the GMRES multi-dots
+// Per-chain reductions split each chain into chunks of SEG_ROWS rows, so that
+// a large chain fills the chip and a chain's summation order does not depend
+// on the other chains of its batch.
+constexpr int SEG_ROWS = 4096;
 constexpr int WS = 64;            // stride of the per-chain TV weights
 constexpr int KV = 16;            // stride of the per-chain eigen tables
 constexpr int SCS = 16;           // stride of the per-chain scalars
@@ -152,6 +154,7 @@ struct Csr {
 template <typename T>
 struct Level {
     int nch = 0, ncont = 0;          // present chains, chains with a next level
+    int segp = 1;                    // reduction chunks of its largest chain
     int rows = 0, cont_rows = 0;     // all rows, rows of continuing chains
     std::vector<ChainGeo> geo;       // host copy
     ChainGeo* dgeo = nullptr;        // device copy
@@ -247,6 +250,7 @@ struct Engine : bamg_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_s = nullptr;     // capture needs a stream other than the legacy default one
+    bool cycle_decided = false, use_graph = false;
     // profiling
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_sweep, ev_gal, ev_ls;
 
@@ -288,11 +292,13 @@ struct Engine : bamg_ctx {
     // per-chain reduction over the finest rows -> out[c * SCS]
     template <int OP>
     void seg_reduce(const double* a, const double* b, double* out) {
-        dim3 grid(SEG_PARTS, nch);
-        hipLaunchKernelGGL(k_seg_reduce_partial<OP>, grid, dim3(BAMG_BLK), 0, s, (const ChainGeo*)L[0].dgeo, a, b,
-                           part);
+        const int P = L[0].segp;
+        dim3 grid(P, nch);
+        hipLaunchKernelGGL(k_seg_reduce_partial<OP>, grid, dim3(BAMG_BLK), 0, s, (const ChainGeo*)L[0].dgeo, SEG_ROWS,
+                           a, b, part);
         HIPCHK(hipGetLastError());
-        LAUNCH(k_seg_reduce_final, nch, BAMG_BLK, s, SEG_PARTS, (const double*)part, out, SCS);
+        LAUNCH(k_seg_reduce_final, nch, BAMG_BLK, s, (const ChainGeo*)L[0].dgeo, SEG_ROWS, P, (const double*)part,
+               out, SCS);
     }
 
     std::pair<hipEvent_t, hipEvent_t> ev_begin() {
@@ -333,6 +339,7 @@ struct Engine : bamg_ctx {
                 off += gg.n;
             }
             lv.nch = (int)lv.geo.size();
+            for (auto& gg : lv.geo) lv.segp = std::max(lv.segp, ceil_div(gg.n, SEG_ROWS));
             lv.rows = off;
             lv.cont_rows = lv.ncont < lv.nch ? lv.geo[lv.ncont].off : off;
         }
@@ -456,10 +463,12 @@ struct Engine : bamg_ctx {
         zero(ent_col, sizeof(int) * nch * KV);
         x0 = A.alloc<double>(n);
         {
+            const size_t P = L[0].segp;
             size_t need = 4096;
-            need = std::max(need, (size_t)nch * SEG_PARTS * 2 * WS);
-            need = std::max(need, (size_t)nch * SEG_PARTS * KV * 4);
-            need = std::max(need, (size_t)nch * MDOT_PARTS * (BAMG_BLK / BAMG_WAVE) * (o.gmres_m + 2));
+            need = std::max(need, (size_t)nch * P * 2 * WS);
+            need = std::max(need, (size_t)nch * P * KV * 4);
+            need = std::max(need, (size_t)nch * P * (BAMG_BLK / BAMG_WAVE) * (o.gmres_m + 2));
+            need = std::max(need, (size_t)nch * 64);
             part = A.alloc<double>(need);
         }
         sc = A.alloc<double>((size_t)nch * SCS);
@@ -525,13 +534,15 @@ struct Engine : bamg_ctx {
     // TV weights of the continuing chains of level l.
     void tv_weights(int l, int use_v) {
         auto& lv = L[l];
-        dim3 grid(SEG_PARTS, lv.ncont);
-        hipLaunchKernelGGL((k_colnorm_partial<T, T>), grid, dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo, r, use_v,
+        dim3 grid(lv.segp, lv.ncont);
+        hipLaunchKernelGGL((k_colnorm_partial<T, T>), grid, dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo, SEG_ROWS,
+                           r, use_v,
                            (const int*)nvc, VS, lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const T*)lv.U, (const T*)lv.V,
                            WS, part);
         HIPCHK(hipGetLastError());
         dim3 g2(r + (use_v ? nvmax : 0), lv.ncont);
-        hipLaunchKernelGGL(k_colnorm_final, g2, dim3(BAMG_BLK), 0, s, SEG_PARTS, r, use_v, (const int*)nvc, WS,
+        hipLaunchKernelGGL(k_colnorm_final, g2, dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo, SEG_ROWS, lv.segp, r,
+                           use_v, (const int*)nvc, WS,
                            (const double*)part, wts);
         HIPCHK(hipGetLastError());
     }
@@ -583,8 +594,9 @@ struct Engine : bamg_ctx {
         const dim3 gv(nblk(maxnL), nch);
         hipLaunchKernelGGL(k_cz_densify<T>, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, Wp, bcolp);
         HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_cz_absmax, dim3(1, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, (const double*)Wp,
-                           scale);
+        hipLaunchKernelGGL(k_cz_absmax_partial, dim3(64, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd,
+                           (const double*)Wp, part);
+        LAUNCH(k_cz_absmax_final, nch, BAMG_BLK, s, 64, (const double*)part, scale);
         HIPCHK(hipGetLastError());
         {
             std::vector<double> big(nch, 1e300);
@@ -766,11 +778,12 @@ struct Engine : bamg_ctx {
             }
             if (a != lv.V) HIPCHK(hipMemcpyAsync(lv.V, a, sizeof(T) * tot, hipMemcpyDeviceToDevice, s));
             if (nvmax > 1) {
-                hipLaunchKernelGGL((k_rayleigh_partial<T, T>), dim3(SEG_PARTS, lv.ncont), dim3(BAMG_BLK), 0, s,
+                hipLaunchKernelGGL((k_rayleigh_partial<T, T>), dim3(lv.segp, lv.ncont), dim3(BAMG_BLK), 0, s,
                                    (const ChainGeo*)lv.dgeo, VS, KV, (const int*)nentc, (const int*)ent_col,
                                    (const int*)kind, lv.B.rp, lv.B.ci, (const T*)lv.B.v, lv.Tm.rp, lv.Tm.ci,
-                                   (const T*)lv.Tm.v, (const T*)lv.V, part);
-                hipLaunchKernelGGL(k_rayleigh_final, dim3(KV, lv.ncont), dim3(BAMG_BLK), 0, s, SEG_PARTS, KV,
+                                   (const T*)lv.Tm.v, (const T*)lv.V, SEG_ROWS, part);
+                hipLaunchKernelGGL(k_rayleigh_final, dim3(KV, lv.ncont), dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo,
+                                   SEG_ROWS, lv.segp, KV,
                                    (const int*)nentc, (const int*)ent_col, (const int*)kind, (const double*)part, lam);
                 HIPCHK(hipGetLastError());
             }
@@ -936,7 +949,43 @@ struct Engine : bamg_ctx {
     }
 
     // One cycle from L[0].f into L[0].e, replayed from a captured graph.
+    // How a cycle is issued: options.cycle_mode 1 = eager launches, 2 = one
+    // captured graph replayed per cycle, 0 = decide on the first cycle: it
+    // runs eagerly, timed on the host (launch cost) and on the stream (GPU
+    // time); the graph is used when launching takes over half the GPU time,
+    // i.e. when the cycle is launch-bound (small chains, coarse levels).
     void run_cycle() {
+        if (!cycle_decided) {
+            cycle_decided = true;
+            if (o.cycle_mode == 1 || o.cycle_mode == 2) {
+                use_graph = o.cycle_mode == 2;
+            } else {
+                hipEvent_t a, b;
+                HIPCHK(hipEventCreate(&a));
+                HIPCHK(hipEventCreate(&b));
+                HIPCHK(hipEventRecord(a, s));
+                auto t0 = std::chrono::steady_clock::now();
+                vcycle(0);
+                const double host_us =
+                    std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+                HIPCHK(hipEventRecord(b, s));
+                HIPCHK(hipEventSynchronize(b));
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, a, b));
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+                st.cycle_host_us = host_us;
+                st.cycle_gpu_us = 1e3 * ms;
+                use_graph = host_us > 0.5 * 1e3 * ms;
+                st.cycle_graph = use_graph ? 1 : 0;
+                return;                          // this cycle has run
+            }
+            st.cycle_graph = use_graph ? 1 : 0;
+        }
+        if (!use_graph) {
+            vcycle(0);
+            return;
+        }
         if (!gexec) {
             // Record the launches of one cycle on a private stream (nothing
             // runs during capture), then replay the graph on the handle's
@@ -1077,10 +1126,11 @@ struct Engine : bamg_ctx {
                 ++inf.cycles;
                 LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)zj, 1.0, wk);
                 for (int pass = 0; pass < 2; ++pass) {
-                    hipLaunchKernelGGL(k_seg_mdot_partial, dim3(MDOT_PARTS, nch), dim3(BAMG_BLK), 0, s, g0, N, j + 1,
+                    hipLaunchKernelGGL(k_seg_mdot_partial, dim3(L[0].segp, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS,
+                                       N, j + 1,
                                        (const int*)act, (const double*)Vk, (const double*)wk, part);
-                    hipLaunchKernelGGL(k_seg_mdot_final, dim3(j + 1, nch), dim3(BAMG_BLK), 0, s,
-                                       MDOT_PARTS * (BAMG_BLK / BAMG_WAVE), j + 1, (const int*)act, (const double*)part,
+                    hipLaunchKernelGGL(k_seg_mdot_final, dim3(j + 1, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS,
+                                       L[0].segp, j + 1, (const int*)act, (const double*)part,
                                        hbuf, GS, Hg + (size_t)j * ld, HSg);
                     HIPCHK(hipGetLastError());
                     LAUNCH(k_seg_vupdate, nb, BAMG_BLK, s, N, g0, nch, j + 1, (const int*)act, (const double*)Vk,
@@ -1238,11 +1288,25 @@ void check_options(const bamg_options& o) {
     if (o.nu_setup < 0 || o.nu_pre < 0 || o.nu_post < 0 || !(o.omega > 0) || o.caliber < 1 || o.n_eig < 1 ||
         o.n_eig > 8 || o.gmres_m < 1 || o.gmres_m > 200 || o.arnoldi_m < 1 || o.levels < 0 || o.coarse_max < 1)
         fail(BAMG_EINVAL, "invalid options");
+    if (o.cycle_mode < 0 || o.cycle_mode > 2) fail(BAMG_EINVAL, "cycle_mode %d not in {0, 1, 2}", o.cycle_mode);
     if (o.interp != BAMG_INTERP_LS) fail(BAMG_EUNSUPPORTED, "interpolation mode %d not available", o.interp);
     if (o.precision != BAMG_FP64 && o.precision != BAMG_MIXED) fail(BAMG_EINVAL, "unknown precision %d", o.precision);
 }
 
+// Memory a handle frees goes back to the device's default stream-ordered pool
+// and stays there (release threshold = unlimited), so that the next setup of
+// similar size reuses mapped memory instead of mapping it again.
+void keep_pool_memory() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess || !pool) return;
+    uint64_t thr = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+}
+
 bamg_ctx* make_ctx(const bamg_options& o) {
+    keep_pool_memory();
     if (o.precision == BAMG_MIXED) return new Engine<float>();
     return new Engine<double>();
 }

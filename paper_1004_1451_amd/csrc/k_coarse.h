@@ -45,20 +45,37 @@ __global__ void k_cz_densify(const CoarseDesc* __restrict__ cd, double* __restri
     }
 }
 
-// max |B_L| per chain (one block per chain) -> scale[chain].
-__global__ void k_cz_absmax(const CoarseDesc* __restrict__ cd, const double* __restrict__ Wp, double* __restrict__ scale) {
+// max |B_L| per chain: block maxima over a grid-stride range (grid (P, nch))
+// into part[chain * P + block], then one block per chain -> scale[chain].
+__global__ void k_cz_absmax_partial(const CoarseDesc* __restrict__ cd, const double* __restrict__ Wp,
+                                    double* __restrict__ part) {
     __shared__ double sh[BAMG_BLK];
     const CoarseDesc d = cd[blockIdx.y];
     const double* W = Wp + d.woff;
     double m = 0;
-    for (long long e = threadIdx.x; e < (long long)d.n * d.n; e += BAMG_BLK) m = fmax(m, fabs(W[e]));
+    const long long nn = (long long)d.n * d.n;
+    for (long long e = (long long)blockIdx.x * BAMG_BLK + threadIdx.x; e < nn; e += (long long)gridDim.x * BAMG_BLK)
+        m = fmax(m, fabs(W[e]));
     sh[threadIdx.x] = m;
     __syncthreads();
     for (int s = BAMG_BLK / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) scale[blockIdx.y] = sh[0];
+    if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = sh[0];
+}
+
+__global__ void k_cz_absmax_final(int P, const double* __restrict__ part, double* __restrict__ scale) {
+    __shared__ double sh[BAMG_BLK];
+    double m = 0;
+    for (int j = threadIdx.x; j < P; j += BAMG_BLK) m = fmax(m, part[(size_t)blockIdx.x * P + j]);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = BAMG_BLK / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) scale[blockIdx.x] = sh[0];
 }
 
 // ---------------------------------------------------------------- block LU

@@ -228,12 +228,11 @@ __global__ void k_f2d(int n, const float* __restrict__ a, double* __restrict__ b
 // out[c * stride].
 
 template <int OP>
-__global__ void k_seg_reduce_partial(const ChainGeo* __restrict__ geo, const double* __restrict__ a,
+__global__ void k_seg_reduce_partial(const ChainGeo* __restrict__ geo, int seg_rows, const double* __restrict__ a,
                                      const double* __restrict__ b, double* __restrict__ part) {
     __shared__ double sh[BAMG_BLK / BAMG_WAVE];
     const ChainGeo g = geo[blockIdx.y];
-    const int chunk = (g.n + gridDim.x - 1) / gridDim.x;
-    const int r0 = g.off + blockIdx.x * chunk, r1 = min(g.off + g.n, r0 + chunk);
+    const int r0 = g.off + blockIdx.x * seg_rows, r1 = min(g.off + g.n, r0 + seg_rows);
     double s = 0;
     for (int i = r0 + threadIdx.x; i < r1; i += BAMG_BLK) {
         double v = a[i];
@@ -246,24 +245,27 @@ __global__ void k_seg_reduce_partial(const ChainGeo* __restrict__ geo, const dou
     if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
-__global__ void k_seg_reduce_final(int nparts, const double* __restrict__ part, double* __restrict__ out, int stride) {
+// Block c adds chain c's ceil(n_c / seg_rows) partials (stride P) in order.
+__global__ void k_seg_reduce_final(const ChainGeo* __restrict__ geo, int seg_rows, int P,
+                                   const double* __restrict__ part, double* __restrict__ out, int stride) {
     __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    const int np = (geo[blockIdx.x].n + seg_rows - 1) / seg_rows;
     double s = 0;
-    for (int j = threadIdx.x; j < nparts; j += BAMG_BLK) s += part[(size_t)blockIdx.x * nparts + j];
+    for (int j = threadIdx.x; j < np; j += BAMG_BLK) s += part[(size_t)blockIdx.x * P + j];
     s = block_sum(s, sh);
     if (threadIdx.x == 0) out[(size_t)blockIdx.x * stride] = s;
 }
 
 // Multi-dots per chain: part[c][chunk*4 + wave][nv] (wave partials, no
-// block barrier); only chains with act[c] != 0.
+// block barrier); only chains with act[c] != 0.  Chunk = seg_rows rows.
 __global__ void __launch_bounds__(BAMG_BLK)
-k_seg_mdot_partial(const ChainGeo* __restrict__ geo, int N, int nv, const int* __restrict__ act,
+k_seg_mdot_partial(const ChainGeo* __restrict__ geo, int seg_rows, int N, int nv, const int* __restrict__ act,
                    const double* __restrict__ V, const double* __restrict__ w, double* __restrict__ part) {
     const ChainGeo g = geo[blockIdx.y];
     if (!act[blockIdx.y]) return;
     const int lane = threadIdx.x % BAMG_WAVE, wv = threadIdx.x / BAMG_WAVE;
-    const int chunk = (g.n + gridDim.x - 1) / gridDim.x;
-    const int i0 = g.off + blockIdx.x * chunk, i1 = min(g.off + g.n, i0 + chunk);
+    const int i0 = g.off + blockIdx.x * seg_rows, i1 = min(g.off + g.n, i0 + seg_rows);
+    if (i0 >= i1) return;
     const size_t slot = (((size_t)blockIdx.y * gridDim.x + blockIdx.x) * (BAMG_BLK / BAMG_WAVE) + wv) * nv;
     for (int b = 0; b < nv; ++b) {
         const double* vb = V + (size_t)b * N;
@@ -274,14 +276,18 @@ k_seg_mdot_partial(const ChainGeo* __restrict__ geo, int N, int nv, const int* _
     }
 }
 
-// h[c*HS + b] = sum of the partials; hacc[c*HAS + b] += h.  Block (b, c).
-__global__ void k_seg_mdot_final(int nparts, int nv, const int* __restrict__ act, const double* __restrict__ part,
-                                 double* __restrict__ h, int HS, double* __restrict__ hacc, int HAS) {
+// h[c*HS + b] = sum of chain c's wave partials (its own chunk count, stride
+// P chunks); hacc[c*HAS + b] += h.  Block (b, c).
+__global__ void k_seg_mdot_final(const ChainGeo* __restrict__ geo, int seg_rows, int P, int nv,
+                                 const int* __restrict__ act, const double* __restrict__ part, double* __restrict__ h,
+                                 int HS, double* __restrict__ hacc, int HAS) {
     __shared__ double sh[BAMG_BLK / BAMG_WAVE];
     const int b = blockIdx.x, c = blockIdx.y;
     if (!act[c]) return;
+    const int WPB = BAMG_BLK / BAMG_WAVE;
+    const int np = ((geo[c].n + seg_rows - 1) / seg_rows) * WPB;
     double s = 0;
-    for (int j = threadIdx.x; j < nparts; j += BAMG_BLK) s += part[((size_t)c * nparts + j) * nv + b];
+    for (int j = threadIdx.x; j < np; j += BAMG_BLK) s += part[((size_t)c * P * WPB + j) * nv + b];
     s = block_sum(s, sh);
     if (threadIdx.x == 0) {
         h[(size_t)c * HS + b] = s;

@@ -298,22 +298,22 @@ __global__ void k_interp(int n, int R, FastDiv divR, const int* __restrict__ pc,
 }
 
 // ---------------------------------------------------------------- TV weights
-// Stage 1, per chain (blockIdx.y) and fixed row chunk (blockIdx.x): partial
+// Stage 1, per chain (blockIdx.y) and row chunk of seg_rows (blockIdx.x): partial
 // sums of (B x_k)_i^2 and (x_k)_i^2 for the chain's columns k of X = [U | V]
 // (U: Ru columns, ld Ru; V: nv_c columns, ld VS; V unused when use_v == 0),
 // eight columns per pass.  part: [chain][chunk][2 * WS].
 #define COL_CHUNK 8
 template <typename T, typename M>
 __global__ void __launch_bounds__(BAMG_BLK)
-k_colnorm_partial(const ChainGeo* __restrict__ geo, int Ru, int use_v, const int* __restrict__ nvc, int VS,
-                  const int* __restrict__ rp, const int* __restrict__ ci, const M* __restrict__ v,
+k_colnorm_partial(const ChainGeo* __restrict__ geo, int seg_rows, int Ru, int use_v, const int* __restrict__ nvc,
+                  int VS, const int* __restrict__ rp, const int* __restrict__ ci, const M* __restrict__ v,
                   const T* __restrict__ U, const T* __restrict__ V, int WS, double* __restrict__ part) {
     __shared__ double sh[BAMG_BLK / BAMG_WAVE];
     const int c = blockIdx.y;
     const ChainGeo g = geo[c];
     const int R = Ru + (use_v ? nvc[c] : 0);
-    const int chunk = (g.n + gridDim.x - 1) / gridDim.x;
-    const int r0 = g.off + blockIdx.x * chunk, r1 = min(g.off + g.n, r0 + chunk);
+    const int r0 = g.off + blockIdx.x * seg_rows, r1 = min(g.off + g.n, r0 + seg_rows);
+    if (r0 >= r1) return;                 // beyond this chain's own chunks
     double* out = part + ((size_t)c * gridDim.x + blockIdx.x) * 2 * WS;
     for (int k0 = 0; k0 < R; k0 += COL_CHUNK) {
         double sr[COL_CHUNK], sx[COL_CHUNK];
@@ -354,15 +354,17 @@ k_colnorm_partial(const ChainGeo* __restrict__ geo, int Ru, int use_v, const int
 
 // Stage 2: block (chain c, column k) adds the chunk partials in order;
 // w_k = 1 / max(||B x_k||^2, (1e-14 ||x_k||)^2) (Section 3.2).
-__global__ void k_colnorm_final(int nchunks, int Ru, int use_v, const int* __restrict__ nvc, int WS,
-                                const double* __restrict__ part, double* __restrict__ w) {
+__global__ void k_colnorm_final(const ChainGeo* __restrict__ geo, int seg_rows, int P, int Ru, int use_v,
+                                const int* __restrict__ nvc, int WS, const double* __restrict__ part,
+                                double* __restrict__ w) {
     __shared__ double sh[BAMG_BLK / BAMG_WAVE];
     const int c = blockIdx.y, k = blockIdx.x;
     const int R = Ru + (use_v ? nvc[c] : 0);
     if (k >= R) return;
+    const int nchunks = (geo[c].n + seg_rows - 1) / seg_rows;
     double a = 0, b = 0;
     for (int j = threadIdx.x; j < nchunks; j += BAMG_BLK) {
-        const double* p = part + ((size_t)c * nchunks + j) * 2 * WS;
+        const double* p = part + ((size_t)c * P + j) * 2 * WS;
         a += p[k];
         b += p[WS + k];
     }
@@ -821,23 +823,23 @@ k_eig_relax(int n, const ChainGeo* __restrict__ geo, int nch, int R, const int* 
     }
 }
 
-// Rayleigh quotient partials, per chain (blockIdx.y) and fixed row chunk
-// (blockIdx.x): for entry e (first column ent_col[e]; a pair uses two) the
+// Rayleigh quotient partials, per chain (blockIdx.y) and row chunk of
+// seg_rows (blockIdx.x): for entry e (first column ent_col[e]; a pair uses two) the
 // sums x^H B x and x^H T x (re, im) -> part[chain][chunk][entry][4].
 template <typename T, typename M>
 __global__ void k_rayleigh_partial(const ChainGeo* __restrict__ geo, int R, int KV, const int* __restrict__ nentc,
                                    const int* __restrict__ ent_colall, const int* __restrict__ kindall,
                                    const int* __restrict__ brp, const int* __restrict__ bci, const M* __restrict__ bv,
                                    const int* __restrict__ trp, const int* __restrict__ tci, const M* __restrict__ tv,
-                                   const T* __restrict__ X, double* __restrict__ part) {
+                                   const T* __restrict__ X, int seg_rows, double* __restrict__ part) {
     __shared__ double sh[BAMG_BLK / BAMG_WAVE];
     const int chn = blockIdx.y;
     const ChainGeo g = geo[chn];
     const int nent = nentc[chn];
     const int* ent_col = ent_colall + (size_t)chn * KV;
     const int* kind = kindall + (size_t)chn * KV;
-    const int chunk = (g.n + gridDim.x - 1) / gridDim.x;
-    const int r0 = g.off + blockIdx.x * chunk, r1 = min(g.off + g.n, r0 + chunk);
+    const int r0 = g.off + blockIdx.x * seg_rows, r1 = min(g.off + g.n, r0 + seg_rows);
+    if (r0 >= r1) return;
     for (int e = 0; e < nent; ++e) {
         int c = ent_col[e];
         bool pair = kind[c] == 1;
@@ -875,15 +877,17 @@ __global__ void k_rayleigh_partial(const ChainGeo* __restrict__ geo, int R, int 
 
 // lam_e = (x^H B x) / (x^H T x) for every entry except the null vector
 // (entry 0 keeps lam = 0); real columns keep a real lam.  Block (e, chain).
-__global__ void k_rayleigh_final(int nchunks, int KV, const int* __restrict__ nentc, const int* __restrict__ ent_colall,
+__global__ void k_rayleigh_final(const ChainGeo* __restrict__ geo, int seg_rows, int P, int KV,
+                                 const int* __restrict__ nentc, const int* __restrict__ ent_colall,
                                  const int* __restrict__ kindall, const double* __restrict__ part,
                                  double* __restrict__ lamall) {
     __shared__ double sh[BAMG_BLK / BAMG_WAVE];
     const int e = blockIdx.x, chn = blockIdx.y;
     if (e >= nentc[chn] || e == 0) return;
+    const int nchunks = (geo[chn].n + seg_rows - 1) / seg_rows;
     double s[4] = {0, 0, 0, 0};
     for (int j = threadIdx.x; j < nchunks; j += BAMG_BLK)
-        for (int q = 0; q < 4; ++q) s[q] += part[(((size_t)chn * nchunks + j) * KV + e) * 4 + q];
+        for (int q = 0; q < 4; ++q) s[q] += part[(((size_t)chn * P + j) * KV + e) * 4 + q];
     for (int q = 0; q < 4; ++q) s[q] = block_sum(s[q], sh);
     if (threadIdx.x == 0) {
         const int* ent_col = ent_colall + (size_t)chn * KV;

@@ -39,3 +39,34 @@ def test_null_arguments_fail_without_gpu():
     assert b"NULL" in lib.bamg_last_error()
     assert lib.bamg_free(None) == B.OK
     assert lib.bamg_solve(None, None, 1e-10, 1, 0, None) == B.EINVAL
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # the ctypes mirrors have the size and field offsets the C compiler gives
+    import ctypes as C
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        import pytest
+        pytest.skip("no C compiler")
+    structs = {"bamg_grid": B.Grid, "bamg_options": B.Options, "bamg_solve_info": B.SolveInfo,
+               "bamg_stats": B.Stats, "bamg_level_info": B.LevelInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bamg.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in out:
+        if not line:
+            continue
+        cname, what, val = line.split()
+        py = structs[cname]
+        got = C.sizeof(py) if what == "size" else getattr(py, what).offset
+        assert got == int(val), (cname, what, got, val)

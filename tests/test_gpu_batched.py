@@ -119,7 +119,7 @@ def test_cycle_graph_replays_match_eager_and_oracle():
     # work on the stream (a full solve) must give the same vector each time
     ch = C.tandem_queue(40)
     levels = 3
-    h = B.Hierarchy.from_chain(ch, 12, B.default_options(levels=levels))
+    h = B.Hierarchy.from_chain(ch, 12, B.default_options(levels=levels, cycle_mode=2))
     lvls = []
     plan = O.level_plan(_grid(ch), levels)
     for l in range(levels):
@@ -144,6 +144,30 @@ def test_cycle_graph_replays_match_eager_and_oracle():
     for rep in range(3):
         assert np.array_equal(outs[rep], outs[0]), rep
         assert np.abs(outs[rep] - want).max() <= 1e-9 * np.abs(want).max(), rep
+    assert h.stats().cycle_graph == 1
+    # eager launches of the same cycle give the same vector
+    he = B.Hierarchy.from_chain(ch, 12, B.default_options(levels=levels, cycle_mode=1))
+    e = torch.empty_like(f)
+    he.apply_vcycle(f, e)
+    assert np.array_equal(e.cpu().numpy(), outs[0])
+    assert he.stats().cycle_graph == 0
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_cycle_modes_give_the_same_solve(mode):
+    chains = _mix()
+    h = B.BatchedHierarchy(chains, R, B.default_options(levels=0, coarse_max=COARSE_MAX, cycle_mode=mode))
+    x = torch.empty(h.n, dtype=torch.float64, device="cuda")
+    info, status, _ = h.solve_batched(x, tol=1e-12, max_cycles=300)
+    assert info.converged
+    h1 = B.BatchedHierarchy(chains, R, B.default_options(levels=0, coarse_max=COARSE_MAX, cycle_mode=1))
+    x1 = torch.empty(h.n, dtype=torch.float64, device="cuda")
+    info1, _, _ = h1.solve_batched(x1, tol=1e-12, max_cycles=300)
+    assert info.cycles == info1.cycles
+    assert torch.equal(x, x1)
+    st = h.stats()
+    if mode == 0:
+        assert st.cycle_gpu_us > 0 and st.cycle_host_us > 0
 
 
 @pytest.mark.parametrize("precision", [B.FP64, B.MIXED])
