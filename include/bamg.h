@@ -210,10 +210,15 @@ int bamg_solve_batched(bamg_handle h, double* x, double tol, int32_t max_cycles,
                        uint32_t flags, int32_t* chain_status,
                        double* chain_residual, bamg_solve_info* info);
 
-/* Release everything the handle owns.  NULL is allowed.  Device memory goes
-   back to the device's default stream-ordered pool, which the library sets to
-   keep freed memory for reuse (hipMemPoolAttrReleaseThreshold = max). */
+/* Release everything the handle owns.  NULL is allowed.  The handle's stream
+   is drained first; its device buffers go back to the library's process-wide
+   cache (per device, size classes within 1/16 of a power of two) for the next
+   setup, and are returned to HIP only by bamg_trim. */
 int bamg_free(bamg_handle h);
+
+/* Return every cached device buffer not owned by a live handle to HIP
+   (hipFree).  Handles stay valid.  Returns 0. */
+int bamg_trim(void);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* bamg_last_error(void);

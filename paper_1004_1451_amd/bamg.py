@@ -30,7 +30,7 @@ ERROR_NAMES = {EINVAL: "EINVAL", ENOTSTOCH: "ENOTSTOCH", EZERODIAG: "EZERODIAG",
 # every symbol include/bamg.h declares
 EXPORTS = ["bamg_options_default", "bamg_setup", "bamg_solve", "bamg_free", "bamg_last_error", "bamg_get_stats",
            "bamg_level_info_get", "bamg_export", "bamg_apply_vcycle", "bamg_relax", "bamg_setup_batched",
-           "bamg_solve_batched"]
+           "bamg_solve_batched", "bamg_trim"]
 
 
 class BamgError(RuntimeError):
@@ -109,6 +109,8 @@ def load():
     lib.bamg_setup_batched.restype = C.c_int
     lib.bamg_solve_batched.argtypes = [vp, vp, dbl, i32, C.c_uint32, vp, vp, C.POINTER(SolveInfo)]
     lib.bamg_solve_batched.restype = C.c_int
+    lib.bamg_trim.argtypes = []
+    lib.bamg_trim.restype = C.c_int
     _lib = lib
     return lib
 
@@ -264,6 +266,11 @@ class BatchedHierarchy(Hierarchy):
                                        resid.ctypes.data_as(C.c_void_p), C.byref(info))
         _check(rc, allow=(ENOCONV,))
         return info, status, resid
+
+
+def trim():
+    """Return the library's cached device buffers to HIP."""
+    _check(load().bamg_trim())
 
 
 def relax(row_ptr, col_idx, val, X, R, omega=0.7, nu=1, F=None, stream=None):

@@ -19,6 +19,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <stdexcept>
 #include <string>
@@ -67,6 +69,9 @@ inline int nblk(long long n) { return (int)std::max<long long>(1, (n + BAMG_BLK 
 // a large chain fills the chip and a chain's summation order does not depend
 // on the other chains of its batch.
 constexpr int SEG_ROWS = 4096;
+// The TV-weight and Rayleigh partials do a sparse product per (row, column)
+// on top of the sum: shorter chunks keep many workgroups in flight.
+constexpr int CN_ROWS = 256;
 constexpr int WS = 64;            // stride of the per-chain TV weights
 constexpr int KV = 16;            // stride of the per-chain eigen tables
 constexpr int SCS = 16;           // stride of the per-chain scalars
@@ -109,24 +114,79 @@ bool poison_enabled() {
     return e && e[0] == '1';
 }
 
+// Process-wide cache of device buffers, per device, in size classes of a
+// sixteenth of an octave (at most 6.25% rounding).  A handle's buffers go
+// back to the cache when it is freed (after its stream has drained) and are
+// handed to the next request of the same class, so repeated setups make no
+// runtime allocation calls.  bamg_trim() returns cached buffers to HIP.
+struct DeviceCache {
+    std::mutex mu;
+    std::map<std::pair<int, size_t>, std::vector<void*>> idle;
+    static size_t size_class(size_t b) {
+        if (b <= 4096) return 4096;
+        const int lg = 63 - __builtin_clzll(b);
+        const size_t g = size_t(1) << (lg - 4);
+        return (b + g - 1) / g * g;
+    }
+    void* get(int dev, size_t cls) {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            auto it = idle.find({dev, cls});
+            if (it != idle.end() && !it->second.empty()) {
+                void* p = it->second.back();
+                it->second.pop_back();
+                return p;
+            }
+        }
+        void* p = nullptr;
+        if (hipMalloc(&p, cls) == hipSuccess && p) return p;
+        (void)hipGetLastError();
+        trim(dev);                                    // give cached memory back and retry once
+        p = nullptr;
+        if (hipMalloc(&p, cls) == hipSuccess && p) return p;
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    void put(int dev, size_t cls, void* p) {
+        std::lock_guard<std::mutex> lk(mu);
+        idle[{dev, cls}].push_back(p);
+    }
+    void trim(int dev) {                              // dev < 0: every device
+        std::lock_guard<std::mutex> lk(mu);
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        for (auto& kv : idle) {
+            if (dev >= 0 && kv.first.first != dev) continue;
+            if (kv.first.first != cur) (void)hipSetDevice(kv.first.first);
+            for (void* p : kv.second) (void)hipFree(p);
+            kv.second.clear();
+        }
+        (void)hipSetDevice(cur);
+    }
+};
+
+DeviceCache& device_cache() {
+    static DeviceCache* c = new DeviceCache();        // lives until the process ends
+    return *c;
+}
+
 struct Arena {
     hipStream_t s = nullptr;
     size_t bytes = 0, budget = 0;
     bool poison = poison_enabled();
-    std::vector<void*> ptrs;
+    int dev = -1;
+    struct Buf { void* p; size_t cls; };
+    std::vector<Buf> bufs;
     template <typename X>
     X* alloc(size_t count) {
-        size_t b = std::max<size_t>(count, 1) * sizeof(X);
-        b = (b + 255) & ~size_t(255);
-        if (budget && bytes + b > budget) fail(BAMG_ENOMEM, "memory budget of %zu bytes exceeded", budget);
-        void* p = nullptr;
-        if (hipMallocAsync(&p, b, s) != hipSuccess || !p) {
-            (void)hipGetLastError();
-            fail(BAMG_ENOMEM, "device allocation of %zu bytes failed", b);
-        }
-        bytes += b;
-        ptrs.push_back(p);
-        if (poison) HIPCHK(hipMemsetAsync(p, std::is_floating_point<X>::value ? 0xFF : 0x00, b, s));
+        if (dev < 0) HIPCHK(hipGetDevice(&dev));
+        const size_t cls = DeviceCache::size_class(std::max<size_t>(count, 1) * sizeof(X));
+        if (budget && bytes + cls > budget) fail(BAMG_ENOMEM, "memory budget of %zu bytes exceeded", budget);
+        void* p = device_cache().get(dev, cls);
+        if (!p) fail(BAMG_ENOMEM, "device allocation of %zu bytes failed", cls);
+        bytes += cls;
+        bufs.push_back({p, cls});
+        if (poison) HIPCHK(hipMemsetAsync(p, std::is_floating_point<X>::value ? 0xFF : 0x00, cls, s));
         return (X*)p;
     }
     template <typename X>
@@ -135,9 +195,11 @@ struct Arena {
         if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), sizeof(X) * v.size(), hipMemcpyHostToDevice, s));
         return p;
     }
+    // Drain the stream, then hand every buffer back to the cache.
     void release() {
-        for (void* p : ptrs) (void)hipFreeAsync(p, s);
-        ptrs.clear();
+        if (!bufs.empty()) (void)hipStreamSynchronize(s);
+        for (auto& b : bufs) device_cache().put(dev, b.cls, b.p);
+        bufs.clear();
         bytes = 0;
     }
 };
@@ -155,6 +217,7 @@ template <typename T>
 struct Level {
     int nch = 0, ncont = 0;          // present chains, chains with a next level
     int segp = 1;                    // reduction chunks of its largest chain
+    int cnp = 1;                     // CN_ROWS chunks of its largest chain
     int rows = 0, cont_rows = 0;     // all rows, rows of continuing chains
     std::vector<ChainGeo> geo;       // host copy
     ChainGeo* dgeo = nullptr;        // device copy
@@ -168,6 +231,8 @@ struct Level {
     T* V = nullptr;                  // rows x VS eigenvector approximations
     T *e = nullptr, *e2 = nullptr, *f = nullptr, *r = nullptr;   // cycle vectors
     unsigned short* mask = nullptr;
+    unsigned short* qmask = nullptr; // Q's box slots per next-level row (cycle restriction)
+    unsigned char* jcnt = nullptr;   // |J_i| per continuing row
     int* cnt = nullptr;
     bool zero_into_e2 = false;       // first smoothing sweep target (fixed buffers)
 };
@@ -244,7 +309,7 @@ struct Engine : bamg_ctx {
     int m_alloc = 0;
     double *Vk = nullptr, *Zk = nullptr, *wk = nullptr, *Hg = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr,
            *ysol = nullptr, *hbuf = nullptr, *rvec = nullptr, *est = nullptr, *xperm = nullptr;
-    int *act = nullptr, *kd = nullptr;
+    int *act = nullptr, *kd = nullptr, *act2 = nullptr;
     double *vin = nullptr, *vout = nullptr;   // permuted vectors of bamg_apply_vcycle
     // graph of one cycle on fixed buffers
     hipGraph_t graph = nullptr;
@@ -261,7 +326,6 @@ struct Engine : bamg_ctx {
         for (auto* v : {&ev_sweep, &ev_gal, &ev_ls})
             for (auto& p : *v) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
         A.release();
-        (void)hipStreamSynchronize(s);
     }
 
     // -------------------------------------------------------------- helpers
@@ -339,7 +403,10 @@ struct Engine : bamg_ctx {
                 off += gg.n;
             }
             lv.nch = (int)lv.geo.size();
-            for (auto& gg : lv.geo) lv.segp = std::max(lv.segp, ceil_div(gg.n, SEG_ROWS));
+            for (auto& gg : lv.geo) {
+                lv.segp = std::max(lv.segp, ceil_div(gg.n, SEG_ROWS));
+                lv.cnp = std::max(lv.cnp, ceil_div(gg.n, CN_ROWS));
+            }
             lv.rows = off;
             lv.cont_rows = lv.ncont < lv.nch ? lv.geo[lv.ncont].off : off;
         }
@@ -387,6 +454,8 @@ struct Engine : bamg_ctx {
                 lv.qc = A.alloc<int>((size_t)nc * 9);
                 lv.qv = A.alloc<T>((size_t)nc * 9);
                 lv.mask = A.alloc<unsigned short>(nc);
+                lv.qmask = A.alloc<unsigned short>(nc);
+                lv.jcnt = A.alloc<unsigned char>(lv.cont_rows);
                 lv.cnt = A.alloc<int>(nc);
             }
         }
@@ -465,8 +534,9 @@ struct Engine : bamg_ctx {
         {
             const size_t P = L[0].segp;
             size_t need = 4096;
-            need = std::max(need, (size_t)nch * P * 2 * WS);
-            need = std::max(need, (size_t)nch * P * KV * 4);
+            const size_t PC = L[0].cnp;
+            need = std::max(need, (size_t)nch * PC * 2 * WS);
+            need = std::max(need, (size_t)nch * PC * KV * 4);
             need = std::max(need, (size_t)nch * P * (BAMG_BLK / BAMG_WAVE) * (o.gmres_m + 2));
             need = std::max(need, (size_t)nch * 64);
             part = A.alloc<double>(need);
@@ -534,14 +604,14 @@ struct Engine : bamg_ctx {
     // TV weights of the continuing chains of level l.
     void tv_weights(int l, int use_v) {
         auto& lv = L[l];
-        dim3 grid(lv.segp, lv.ncont);
-        hipLaunchKernelGGL((k_colnorm_partial<T, T>), grid, dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo, SEG_ROWS,
+        dim3 grid(lv.cnp, lv.ncont);
+        hipLaunchKernelGGL((k_colnorm_partial<T, T>), grid, dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo, CN_ROWS,
                            r, use_v,
                            (const int*)nvc, VS, lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const T*)lv.U, (const T*)lv.V,
                            WS, part);
         HIPCHK(hipGetLastError());
         dim3 g2(r + (use_v ? nvmax : 0), lv.ncont);
-        hipLaunchKernelGGL(k_colnorm_final, g2, dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo, SEG_ROWS, lv.segp, r,
+        hipLaunchKernelGGL(k_colnorm_final, g2, dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo, CN_ROWS, lv.cnp, r,
                            use_v, (const int*)nvc, WS,
                            (const double*)part, wts);
         HIPCHK(hipGetLastError());
@@ -577,10 +647,10 @@ struct Engine : bamg_ctx {
         if (profile) ev = ev_begin();
         LAUNCH((k_ls_fit<T, T>), nblk(lv.cont_rows), BAMG_BLK, s, lv.cont_rows, (const ChainGeo*)lv.dgeo, lv.ncont, r,
                use_v, (const int*)nvc, VS, (const T*)lv.U, (const T*)lv.V, (const double*)wts, WS, o.caliber, lv.pc,
-               lv.pv, inject ? c.U : (T*)nullptr, (int*)nullptr);
+               lv.pv, inject ? c.U : (T*)nullptr, lv.jcnt);
         if (profile) ev_end(ev, ev_ls);
         LAUNCH(k_build_q<T>, nblk(c.rows), BAMG_BLK, s, c.rows, (const ChainGeo*)c.dgeo, (const ChainGeo*)lv.dgeo, c.nch,
-               lv.pc, lv.qc, lv.qv);
+               lv.pc, lv.qc, lv.qv, lv.qmask);
         galerkin(l, profile);
     }
 
@@ -618,20 +688,8 @@ struct Engine : bamg_ctx {
                 HIPCHK(hipGetLastError());
             }
             LAUNCH(k_cz_diag, nch, BAMG_BLK, s, (const CoarseDesc*)cd, -1, Fp, (const double*)scale, minpiv);
-            hipLaunchKernelGGL(k_cz_identity, dim3(nblk((long long)maxnL * maxnL), nch), dim3(BAMG_BLK), 0, s,
-                               (const CoarseDesc*)cd, Wp);
-            const dim3 gs(ceil_div(maxnL, 64), nch);
-            for (int stp = 1; stp + 1 < nxmax; ++stp)
-                hipLaunchKernelGGL(k_cz_strip, gs, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, 0, stp, Wp,
-                                   (const double*)Fp);
-            for (int stp = 0; 2 * stp < nxmax - 2; ++stp)
-                hipLaunchKernelGGL(k_cz_strip, gs, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, 1, stp, Wp,
-                                   (const double*)Fp);
-            hipLaunchKernelGGL(k_cz_strip, gs, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, 2, 0, Wp, (const double*)Fp);
-            hipLaunchKernelGGL(k_cz_strip, gs, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, 3, 0, Wp, (const double*)Fp);
-            for (int stp = 0; stp < nxmax - 1; ++stp)
-                hipLaunchKernelGGL(k_cz_strip, gs, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, 4, stp, Wp,
-                                   (const double*)Fp);
+            hipLaunchKernelGGL(k_cz_subst, dim3(ceil_div(maxnL, 64), nch), dim3(BAMG_BLK), 0, s,
+                               (const CoarseDesc*)cd, Wp, (const double*)Fp);
             HIPCHK(hipGetLastError());
         }
         hipLaunchKernelGGL(k_cz_zero_border, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, Wp);
@@ -771,19 +829,19 @@ struct Engine : bamg_ctx {
             T* a = lv.V;
             T* b = sweep_tmp;
             for (int k = 0; k < o.nu_setup; ++k) {
-                LAUNCH((k_eig_relax<T, T>), nblk(rows), BAMG_BLK, s, rows, (const ChainGeo*)lv.dgeo, lv.ncont, VS,
+                LAUNCH((k_eig_relax<T, T>), nblk(tot), BAMG_BLK, s, rows, (const ChainGeo*)lv.dgeo, lv.ncont, VS, dR,
                        (const int*)nvc, KV, lv.B.rp, lv.B.ci, (const T*)lv.B.v, lv.Tm.rp, lv.Tm.ci, (const T*)lv.Tm.v,
                        (const double*)lam, (const int*)kind, o.omega, (const T*)a, b);
                 std::swap(a, b);
             }
             if (a != lv.V) HIPCHK(hipMemcpyAsync(lv.V, a, sizeof(T) * tot, hipMemcpyDeviceToDevice, s));
             if (nvmax > 1) {
-                hipLaunchKernelGGL((k_rayleigh_partial<T, T>), dim3(lv.segp, lv.ncont), dim3(BAMG_BLK), 0, s,
+                hipLaunchKernelGGL((k_rayleigh_partial<T, T>), dim3(lv.cnp, lv.ncont), dim3(BAMG_BLK), 0, s,
                                    (const ChainGeo*)lv.dgeo, VS, KV, (const int*)nentc, (const int*)ent_col,
                                    (const int*)kind, lv.B.rp, lv.B.ci, (const T*)lv.B.v, lv.Tm.rp, lv.Tm.ci,
-                                   (const T*)lv.Tm.v, (const T*)lv.V, SEG_ROWS, part);
+                                   (const T*)lv.Tm.v, (const T*)lv.V, CN_ROWS, part);
                 hipLaunchKernelGGL(k_rayleigh_final, dim3(KV, lv.ncont), dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo,
-                                   SEG_ROWS, lv.segp, KV,
+                                   CN_ROWS, lv.cnp, KV,
                                    (const int*)nentc, (const int*)ent_col, (const int*)kind, (const double*)part, lam);
                 HIPCHK(hipGetLastError());
             }
@@ -937,7 +995,9 @@ struct Engine : bamg_ctx {
         }
         LAUNCH((k_residual<T, T>), nb, BAMG_BLK, s, rows, lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const T*)cur,
                (const T*)lv.f, lv.r);
-        LAUNCH((k_restrict<T, T>), nblk(c.rows), BAMG_BLK, s, c.rows, lv.qc, (const T*)lv.qv, (const T*)lv.r, c.f);
+        LAUNCH(k_restrict_box<T>, nblk(c.rows), BAMG_BLK, s, c.rows, (const ChainGeo*)c.dgeo,
+               (const ChainGeo*)lv.dgeo, c.nch, (const unsigned short*)lv.qmask, (const unsigned char*)lv.jcnt,
+               (const T*)lv.r, c.f);
         vcycle(l + 1);
         LAUNCH((k_prolong_add<T, T>), nb, BAMG_BLK, s, rows, lv.pc, (const T*)lv.pv, (const T*)c.e, cur);
         for (int k = 0; k < o.nu_post; ++k) {
@@ -1064,6 +1124,7 @@ struct Engine : bamg_ctx {
             hbuf = A.alloc<double>((size_t)nch * GS);
             est = A.alloc<double>(nch);
             act = A.alloc<int>(nch);
+            act2 = A.alloc<int>(nch);
             kd = A.alloc<int>(nch);
             if (reordered) xperm = A.alloc<double>(N);
             m_alloc = m;
@@ -1125,16 +1186,20 @@ struct Engine : bamg_ctx {
                 precondition(vj, zj);
                 ++inf.cycles;
                 LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)zj, 1.0, wk);
+                // classical Gram-Schmidt, second pass only where needed
                 for (int pass = 0; pass < 2; ++pass) {
+                    const int* am = pass == 0 ? act : act2;
+                    const int nv = pass == 0 ? j + 2 : j + 1;       // pass 0 also forms ||w||^2
                     hipLaunchKernelGGL(k_seg_mdot_partial, dim3(L[0].segp, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS,
-                                       N, j + 1,
-                                       (const int*)act, (const double*)Vk, (const double*)wk, part);
-                    hipLaunchKernelGGL(k_seg_mdot_final, dim3(j + 1, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS,
-                                       L[0].segp, j + 1, (const int*)act, (const double*)part,
-                                       hbuf, GS, Hg + (size_t)j * ld, HSg);
+                                       N, j + 1, nv, am, (const double*)Vk, (const double*)wk, part);
+                    hipLaunchKernelGGL(k_seg_mdot_final, dim3(nv, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS,
+                                       L[0].segp, j + 1, nv, am, (const double*)part, hbuf, GS, Hg + (size_t)j * ld,
+                                       HSg);
                     HIPCHK(hipGetLastError());
-                    LAUNCH(k_seg_vupdate, nb, BAMG_BLK, s, N, g0, nch, j + 1, (const int*)act, (const double*)Vk,
+                    LAUNCH(k_seg_vupdate, nb, BAMG_BLK, s, N, g0, nch, j + 1, am, (const double*)Vk,
                            (const double*)hbuf, GS, wk);
+                    if (pass == 0)
+                        LAUNCH(k_seg_dgks, ceil_div(nch, 64), 64, s, nch, j + 1, act, (const double*)hbuf, GS, act2);
                 }
                 seg_reduce<RED_DOT>(wk, wk, sc + 4);
                 LAUNCH(k_seg_scale, nb, BAMG_BLK, s, N, g0, nch, (const int*)act, (const double*)wk,
@@ -1293,20 +1358,7 @@ void check_options(const bamg_options& o) {
     if (o.precision != BAMG_FP64 && o.precision != BAMG_MIXED) fail(BAMG_EINVAL, "unknown precision %d", o.precision);
 }
 
-// Memory a handle frees goes back to the device's default stream-ordered pool
-// and stays there (release threshold = unlimited), so that the next setup of
-// similar size reuses mapped memory instead of mapping it again.
-void keep_pool_memory() {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return;
-    hipMemPool_t pool = nullptr;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess || !pool) return;
-    uint64_t thr = UINT64_MAX;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-}
-
 bamg_ctx* make_ctx(const bamg_options& o) {
-    keep_pool_memory();
     if (o.precision == BAMG_MIXED) return new Engine<float>();
     return new Engine<double>();
 }
@@ -1428,6 +1480,10 @@ int bamg_free(bamg_handle h) {
     return run_guarded([&] { delete h; });
 }
 
+int bamg_trim(void) {
+    return run_guarded([&] { device_cache().trim(-1); });
+}
+
 int bamg_get_stats(bamg_handle h, bamg_stats* st) {
     return run_guarded([&] {
         if (!h || !st) fail(BAMG_EINVAL, "NULL argument");
@@ -1466,7 +1522,7 @@ int bamg_relax(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const 
         A.s = s;
         struct Rel {
             Arena& A;
-            ~Rel() { A.release(); (void)hipStreamSynchronize(A.s); }
+            ~Rel() { A.release(); }
         } rel{A};
         int hr[2];
         HIPCHK(hipMemcpyAsync(&hr[0], row_ptr, sizeof(int), hipMemcpyDeviceToHost, s));

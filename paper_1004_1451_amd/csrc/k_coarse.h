@@ -112,62 +112,68 @@ __global__ void k_cz_extract(const CoarseDesc* __restrict__ cd, const double* __
 }
 
 // Invert diagonal block k of every chain with k < nx (k < 0: the chain's
-// last block).  One workgroup per chain; same Gauss-Jordan as k_gj_diag.
+// last block).  One workgroup per chain: Gauss-Jordan elimination without
+// pivoting on the block padded to 64 x 64 with the identity.  Thread (w, c)
+// keeps column c of rows 16 w .. 16 w + 15 in registers; each step reads the
+// pivot column from the owning lanes (readlane) and the pivot row from LDS,
+// where its owner wave has put it, so the only LDS traffic per step is one
+// row.  Step st, for row r and column c (f = a_r,st, p = a_st,st):
+//   a_st,c <- a_st,c / p,  a_r,st <- -f / p,  a_st,st <- 1 / p,
+//   a_r,c <- a_r,c - f a_st,c / p  (all other entries).
+__device__ __forceinline__ double cz_readlane(double v, int lane) {
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_readlane(lo, lane);
+    hi = __builtin_amdgcn_readlane(hi, lane);
+    return __hiloint2double(hi, lo);
+}
+
 __global__ void __launch_bounds__(BAMG_BLK)
 k_cz_diag(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, const double* __restrict__ scale,
           double* __restrict__ minpiv) {
     const CoarseDesc d = cd[blockIdx.x];
     const int kk = k < 0 ? d.nx - 1 : k;
     if (kk >= d.nx - (k < 0 ? 0 : 1) || d.n < 2) return;
-    __shared__ double M[2][GJ_NB][GJ_NB + 1];
+    __shared__ double prow[2][GJ_NB];
     double* A = cz_blk(Fp, d, 0, kk);
     const int nb = d.ny;
-    const int tid = threadIdx.x;
-    const int r0 = (tid / 16) * 4, c0 = (tid % 16) * 4;
-    double S[4][4];
+    const int c = threadIdx.x % BAMG_WAVE, w = threadIdx.x / BAMG_WAVE;   // column, row block
+    double S[16];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            int r = r0 + a, c = c0 + b;
-            S[a][b] = (r < nb && c < nb) ? A[r * nb + c] : (r == c ? 1.0 : 0.0);
-            M[0][r][c] = S[a][b];
-        }
+    for (int i = 0; i < 16; ++i) {
+        const int r = 16 * w + i;
+        S[i] = (r < nb && c < nb) ? A[r * nb + c] : (r == c ? 1.0 : 0.0);
+    }
     const double sc = scale[blockIdx.x];
     double mp = 1e300;
-    __syncthreads();
-    for (int st = 0; st < GJ_NB; ++st) {
-        const int rd = st & 1, wr = rd ^ 1;
-        const double piv = M[rd][st][st];
-        const double ip = 1.0 / piv;
-        if (tid == 0 && st < nb) mp = fmin(mp, fabs(piv) / sc);
-        double f[4], pr[4];
+    for (int blk = 0; blk < 4; ++blk) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a) f[a] = M[rd][r0 + a][st];
+        for (int ii = 0; ii < 16; ++ii) {
+            const int st = 16 * blk + ii, buf = st & 1;
+            if (w == blk) prow[buf][c] = S[ii];
+            __syncthreads();
+            const double piv = prow[buf][st];
+            const double ip = 1.0 / piv;
+            const double pr = prow[buf][c] * ip;
+            if (threadIdx.x == 0 && st < nb) mp = fmin(mp, fabs(piv) / sc);
+            const bool ck = c == st;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) pr[b] = M[rd][st][c0 + b] * ip;
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const bool rk = (r0 + a) == st, ck = (c0 + b) == st;
-                double v = S[a][b] - f[a] * pr[b];
-                v = ck ? -f[a] * ip : v;
-                v = rk ? pr[b] : v;
+            for (int i = 0; i < 16; ++i) {
+                const double f = cz_readlane(S[i], st);      // a_r,st from lane st
+                const bool rk = (16 * w + i) == st;
+                double v = S[i] - f * pr;
+                v = ck ? -f * ip : v;
+                v = rk ? pr : v;
                 v = (rk && ck) ? ip : v;
-                S[a][b] = v;
-                M[wr][r0 + a][c0 + b] = v;
+                S[i] = v;
             }
-        __syncthreads();
+        }
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            int r = r0 + a, c = c0 + b;
-            if (r < nb && c < nb) A[r * nb + c] = S[a][b];
-        }
-    if (tid == 0) minpiv[blockIdx.x] = fmin(minpiv[blockIdx.x], mp);
+    for (int i = 0; i < 16; ++i) {
+        const int r = 16 * w + i;
+        if (r < nb && c < nb) A[r * nb + c] = S[i];
+    }
+    if (threadIdx.x == 0) minpiv[blockIdx.x] = fmin(minpiv[blockIdx.x], mp);
 }
 
 // One b x b product C = A B (mode 0, C may alias A) or C -= A B (mode 1).
@@ -250,123 +256,153 @@ k_cz_elim(const CoarseDesc* __restrict__ cd, int k, int phase, double* __restric
     cz_gemm(b, A, Bm, C, mode, AsT, Bs);
 }
 
-// W = I on every chain's block.
-__global__ void k_cz_identity(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp) {
-    const CoarseDesc d = cd[blockIdx.y];
-    double* W = Wp + d.woff;
-    const long long nn = (long long)d.n * d.n;
-    for (long long e = (long long)blockIdx.x * BAMG_BLK + threadIdx.x; e < nn; e += (long long)gridDim.x * BAMG_BLK)
-        W[e] = (e / d.n == e % d.n) ? 1.0 : 0.0;
-}
-
-// Block substitution step for every chain (blockIdx.y), column tile
-// blockIdx.x (64 columns):  T = W[kout] - A1 W[j1] - A2 W[j2], then
-// W[kout] = Dinv T.  The operands of each chain follow from (phase, step):
-//   phase 0 (forward, step s >= 1):   kout = s (s < K): A1 = Lo[s], j1 = s-1
-//   phase 1 (forward arrow, j = 2s):  kout = K: A1 = Rw[j], A2 = Rw[j+1]  (j < K-1)
-//   phase 2 (forward last row):       kout = K: A1 = Lo[K], j1 = K-1
-//   phase 3 (backward last row):      kout = K: Dinv_K
-//   phase 4 (backward, step s):       kout = K-1-s: A1 = Up, j1 = kout+1,
-//                                      A2 = Cl (arrow, kout < K-1), j2 = K; Dinv
-__global__ void __launch_bounds__(BAMG_BLK)
-k_cz_strip(const CoarseDesc* __restrict__ cd, int phase, int step, double* __restrict__ Wp,
-           const double* __restrict__ Fp) {
-    __shared__ double Ms[GJ_NB][GJ_NB + 1];
-    __shared__ double Xs[GJ_NB][64 + 1];
-    const CoarseDesc d = cd[blockIdx.y];
-    const int K = d.nx - 1, b = d.ny, n = d.n;
-    const bool arrow = d.periodic && d.nx >= 3;
-    int kout = -1, j1 = 0, j2 = 0;
-    const double *A1 = nullptr, *A2 = nullptr, *Dinv = nullptr;
-    double* F = (double*)Fp;
-    if (n < 2) return;
-    if (phase == 0) {
-        if (step >= 1 && step < K) { kout = step; A1 = cz_blk(F, d, 2, step); j1 = step - 1; }
-    } else if (phase == 1) {
-        const int j = 2 * step;
-        if (arrow && j < K - 1) {
-            kout = K; A1 = cz_blk(F, d, 4, j); j1 = j;
-            if (j + 1 < K - 1) { A2 = cz_blk(F, d, 4, j + 1); j2 = j + 1; }
-        }
-    } else if (phase == 2) {
-        if (K >= 1) { kout = K; A1 = cz_blk(F, d, 2, K); j1 = K - 1; }
-    } else if (phase == 3) {
-        kout = K; Dinv = cz_blk(F, d, 0, K);
-    } else {
-        const int k = K - 1 - step;
-        if (k >= 0) {
-            kout = k; A1 = cz_blk(F, d, 1, k); j1 = k + 1; Dinv = cz_blk(F, d, 0, k);
-            if (arrow && k < K - 1) { A2 = cz_blk(F, d, 3, k); j2 = K; }
-        }
-    }
-    const int c0 = blockIdx.x * 64;
-    if (kout < 0 || c0 >= n) return;
-    double* W = Wp + d.woff;
-    const int tid = threadIdx.x;
-    const int w = min(64, n - c0);
-    const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
-    double T[4][4];
+// All substitution steps of W = (L U)^-1 for one 64-column tile of one chain
+// per workgroup (grid (ceil(n / 64), nch)): the columns of W are independent
+// right-hand sides (the identity), so a workgroup walks every block row on
+// its own, with the previous block row of the solution kept in LDS.
+//   forward:  Y_0 = I_0;  Y_s = I_s - Lo_s Y_{s-1}  (s < K);
+//             Y_K = I_K - sum_{j < K-1} Rw_j Y_j - Lo_K Y_{K-1}  (arrow terms
+//             when periodic), in that order;
+//   backward: X_K = Dinv_K Y_K;
+//             X_k = Dinv_k (Y_k - Up_k X_{k+1} - Cl_k X_K)  (k = K-1 .. 0).
+// Lo_s and Rw_j hold the multipliers (already times Dinv), Dk the inverted
+// diagonal blocks of the LU; every product adds over t in ascending order.
+__device__ __forceinline__ void cz_ident(int blk, int b, int c0, int w, int tr, int tc, double X[4][4]) {
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            int r = tr + a, c = tc + q;
-            T[a][q] = (r < b && c < w) ? W[(size_t)(kout * b + r) * n + c0 + c] : 0.0;
+            const int r = tr + a, c = tc + q;
+            X[a][q] = (r < b && c < w && blk * b + r == c0 + c) ? 1.0 : 0.0;
         }
-    for (int term = 0; term < 2; ++term) {
-        const double* M = term == 0 ? A1 : A2;
-        const int jb = term == 0 ? j1 : j2;
-        if (!M) continue;
-        __syncthreads();
-        for (int e = tid; e < b * b; e += BAMG_BLK) Ms[e / b][e % b] = M[e];
-        for (int e = tid; e < b * 64; e += BAMG_BLK) {
-            int r = e / 64, c = e % 64;
-            Xs[r][c] = c < w ? W[(size_t)(jb * b + r) * n + c0 + c] : 0.0;
-        }
-        __syncthreads();
-        for (int t = 0; t < b; ++t) {
-            double mv[4], xv[4];
+}
+
+// acc (+)= Ms[rows tr.., 0:b] * Xs[0:b, cols tc..]
+__device__ __forceinline__ void cz_mac(int b, const double (*Ms)[GJ_NB + 1], const double (*Xs)[GJ_NB + 1], int tr,
+                                       int tc, double acc[4][4], double sign) {
+    for (int t = 0; t < b; ++t) {
+        double mv[4], xv[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) mv[a] = (tr + a < b) ? Ms[tr + a][t] : 0.0;
+        for (int a = 0; a < 4; ++a) mv[a] = sign * Ms[tr + a][t];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) xv[q] = Xs[t][tc + q];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) T[a][q] -= mv[a] * xv[q];
-        }
-    }
-    if (Dinv) {
-        __syncthreads();
-        for (int e = tid; e < b * b; e += BAMG_BLK) Ms[e / b][e % b] = Dinv[e];
+        for (int q = 0; q < 4; ++q) xv[q] = Xs[t][tc + q];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) Xs[tr + a][tc + q] = T[a][q];
+            for (int q = 0; q < 4; ++q) acc[a][q] += mv[a] * xv[q];
+    }
+}
+
+__device__ __forceinline__ void cz_load_blk(int b, const double* __restrict__ M, double (*Ms)[GJ_NB + 1]) {
+    for (int e = threadIdx.x; e < GJ_NB * GJ_NB; e += BAMG_BLK) {
+        const int r = e / GJ_NB, c = e % GJ_NB;
+        Ms[r][c] = (r < b && c < b) ? M[r * b + c] : 0.0;
+    }
+}
+
+__device__ __forceinline__ void cz_put(const double X[4][4], double (*Xs)[GJ_NB + 1], int tr, int tc) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Xs[tr + a][tc + q] = X[a][q];
+}
+
+__global__ void __launch_bounds__(BAMG_BLK)
+k_cz_subst(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const double* __restrict__ Fp) {
+    __shared__ double Ms[GJ_NB][GJ_NB + 1];
+    __shared__ double Xs[GJ_NB][GJ_NB + 1];
+    __shared__ double Ks[GJ_NB][GJ_NB + 1];
+    const CoarseDesc d = cd[blockIdx.y];
+    const int K = d.nx - 1, b = d.ny, n = d.n;
+    const int c0 = blockIdx.x * 64;
+    if (n < 2 || c0 >= n) return;
+    const bool arrow = d.periodic && d.nx >= 3;
+    double* F = (double*)Fp;
+    double* W = Wp + d.woff;
+    const int w = min(64, n - c0);
+    const int tid = threadIdx.x, tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+    auto store = [&](int blk, const double X[4][4]) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = tr + a, c = tc + q;
+                if (r < b && c < w) W[(size_t)(blk * b + r) * n + c0 + c] = X[a][q];
+            }
+    };
+    double T[4][4], TK[4][4];
+    cz_ident(K, b, c0, w, tr, tc, TK);
+    // forward substitution (L has unit diagonal blocks)
+    for (int s = 0; s < K; ++s) {
+        cz_ident(s, b, c0, w, tr, tc, T);
+        if (s >= 1) {                                // Xs holds Y_{s-1}
+            __syncthreads();
+            cz_load_blk(b, cz_blk(F, d, 2, s), Ms);
+            __syncthreads();
+            cz_mac(b, Ms, Xs, tr, tc, T, -1.0);
+        }
+        __syncthreads();
+        cz_put(T, Xs, tr, tc);
+        store(s, T);
+        if (arrow && s < K - 1) {
+            cz_load_blk(b, cz_blk(F, d, 4, s), Ms);
+            __syncthreads();
+            cz_mac(b, Ms, Xs, tr, tc, TK, -1.0);
+        }
+        if (s == K - 1) {
+            __syncthreads();
+            cz_load_blk(b, cz_blk(F, d, 2, K), Ms);
+            __syncthreads();
+            cz_mac(b, Ms, Xs, tr, tc, TK, -1.0);
+        }
+    }
+    // X_K = Dinv_K Y_K, kept in Ks for the arrow terms
+    __syncthreads();
+    cz_load_blk(b, cz_blk(F, d, 0, K), Ms);
+    cz_put(TK, Xs, tr, tc);
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) T[a][q] = 0.0;
+    cz_mac(b, Ms, Xs, tr, tc, T, 1.0);
+    store(K, T);
+    __syncthreads();
+    cz_put(T, Ks, tr, tc);
+    cz_put(T, Xs, tr, tc);                           // X_{k+1} for k = K-1
+    // backward substitution
+    for (int k = K - 1; k >= 0; --k) {
+        double U[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = tr + a, c = tc + q;
+                U[a][q] = (r < b && c < w) ? W[(size_t)(k * b + r) * n + c0 + c] : 0.0;
+            }
+        __syncthreads();
+        cz_load_blk(b, cz_blk(F, d, 1, k), Ms);
+        __syncthreads();
+        cz_mac(b, Ms, Xs, tr, tc, U, -1.0);
+        if (arrow && k < K - 1) {
+            __syncthreads();
+            cz_load_blk(b, cz_blk(F, d, 3, k), Ms);
+            __syncthreads();
+            cz_mac(b, Ms, Ks, tr, tc, U, -1.0);
+        }
+        __syncthreads();
+        cz_load_blk(b, cz_blk(F, d, 0, k), Ms);
+        cz_put(U, Xs, tr, tc);
         __syncthreads();
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int q = 0; q < 4; ++q) T[a][q] = 0.0;
-        for (int t = 0; t < b; ++t) {
-            double mv[4], xv[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) mv[a] = (tr + a < b) ? Ms[tr + a][t] : 0.0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) xv[q] = Xs[t][tc + q];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) T[a][q] += mv[a] * xv[q];
-        }
+        cz_mac(b, Ms, Xs, tr, tc, T, 1.0);
+        store(k, T);
+        __syncthreads();
+        cz_put(T, Xs, tr, tc);
     }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int r = tr + a, c = tc + q;
-            if (r < b && c < w) W[(size_t)(kout * b + r) * n + c0 + c] = T[a][q];
-        }
 }
 
 // ---------------------------------------------------------------- projections

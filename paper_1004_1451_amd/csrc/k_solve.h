@@ -258,8 +258,9 @@ __global__ void k_seg_reduce_final(const ChainGeo* __restrict__ geo, int seg_row
 
 // Multi-dots per chain: part[c][chunk*4 + wave][nv] (wave partials, no
 // block barrier); only chains with act[c] != 0.  Chunk = seg_rows rows.
+// Dots b < nb are <V_b, w>; with nv = nb + 1 the last one is <w, w>.
 __global__ void __launch_bounds__(BAMG_BLK)
-k_seg_mdot_partial(const ChainGeo* __restrict__ geo, int seg_rows, int N, int nv, const int* __restrict__ act,
+k_seg_mdot_partial(const ChainGeo* __restrict__ geo, int seg_rows, int N, int nb, int nv, const int* __restrict__ act,
                    const double* __restrict__ V, const double* __restrict__ w, double* __restrict__ part) {
     const ChainGeo g = geo[blockIdx.y];
     if (!act[blockIdx.y]) return;
@@ -268,7 +269,7 @@ k_seg_mdot_partial(const ChainGeo* __restrict__ geo, int seg_rows, int N, int nv
     if (i0 >= i1) return;
     const size_t slot = (((size_t)blockIdx.y * gridDim.x + blockIdx.x) * (BAMG_BLK / BAMG_WAVE) + wv) * nv;
     for (int b = 0; b < nv; ++b) {
-        const double* vb = V + (size_t)b * N;
+        const double* vb = b < nb ? V + (size_t)b * N : w;
         double s = 0;
         for (int i = i0 + threadIdx.x; i < i1; i += BAMG_BLK) s += vb[i] * w[i];
         s = wave_sum(s);
@@ -277,8 +278,8 @@ k_seg_mdot_partial(const ChainGeo* __restrict__ geo, int seg_rows, int N, int nv
 }
 
 // h[c*HS + b] = sum of chain c's wave partials (its own chunk count, stride
-// P chunks); hacc[c*HAS + b] += h.  Block (b, c).
-__global__ void k_seg_mdot_final(const ChainGeo* __restrict__ geo, int seg_rows, int P, int nv,
+// P chunks); hacc[c*HAS + b] += h for the basis dots b < nb.  Block (b, c).
+__global__ void k_seg_mdot_final(const ChainGeo* __restrict__ geo, int seg_rows, int P, int nb, int nv,
                                  const int* __restrict__ act, const double* __restrict__ part, double* __restrict__ h,
                                  int HS, double* __restrict__ hacc, int HAS) {
     __shared__ double sh[BAMG_BLK / BAMG_WAVE];
@@ -291,8 +292,27 @@ __global__ void k_seg_mdot_final(const ChainGeo* __restrict__ geo, int seg_rows,
     s = block_sum(s, sh);
     if (threadIdx.x == 0) {
         h[(size_t)c * HS + b] = s;
-        hacc[(size_t)c * HAS + b] += s;
+        if (b < nb) hacc[(size_t)c * HAS + b] += s;
     }
+}
+
+// Second Gram-Schmidt pass only where the first lost more than half of
+// ||w||^2 (the test of Daniel, Gragg, Kaufman and Stewart with eta^2 = 1/2):
+// after w' = w - V h, ||w'||^2 = ||w||^2 - ||h||^2 for orthonormal V.
+// act2[c] = act[c] && ||w||^2 - ||h||^2 < ||w||^2 / 2  (h[c*HS + nb] = ||w||^2).
+__global__ void k_seg_dgks(int nch, int nb, const int* __restrict__ act, const double* __restrict__ h, int HS,
+                           int* __restrict__ act2) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nch) return;
+    int need = 0;
+    if (act[c]) {
+        const double* hc = h + (size_t)c * HS;
+        double hh = 0;
+        for (int b = 0; b < nb; ++b) hh += hc[b] * hc[b];
+        const double ww = hc[nb];
+        need = (ww - hh) < 0.5 * ww;
+    }
+    act2[c] = need;
 }
 
 // w -= sum_b h_b V_b on the rows of active chains.

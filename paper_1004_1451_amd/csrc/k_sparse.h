@@ -265,6 +265,37 @@ __global__ void k_restrict(int nc, const int* __restrict__ qc, const M* __restri
     fc[I] = acc;
 }
 
+// f_c = Q r from the structure of Q alone: coarse row I takes the fine points
+// of its 3x3 box whose bit is set in qmask[I], each with weight 1/|J_i|
+// (jcnt), added in slot order.  Reads 2 bytes per coarse row and 1 per fine
+// row instead of the 108-byte ELL row.
+template <typename T>
+__global__ void k_restrict_box(int nc, const ChainGeo* __restrict__ geoc, const ChainGeo* __restrict__ geof, int nch,
+                               const unsigned short* __restrict__ qmask, const unsigned char* __restrict__ jcnt,
+                               const T* __restrict__ r, T* __restrict__ fc) {
+    int I = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (I >= nc) return;
+    const int ch = find_chain(geoc, nch, I);
+    const ChainGeo gc = geoc[ch];
+    const ChainGeo gf = geof[ch];
+    const int lI = I - gc.off;
+    const int A = (int)gc.dy.div((uint32_t)lI), Bq = lI - A * gc.ny;
+    const unsigned m = qmask[I];
+    T acc = 0;
+#pragma unroll
+    for (int s = 0; s < 9; ++s) {
+        if (!((m >> s) & 1)) continue;
+        int na = 2 * A + s / 3 - 1, nb = 2 * Bq + s % 3 - 1;
+        if (gf.periodic) {
+            na = na < 0 ? na + gf.nx : (na >= gf.nx ? na - gf.nx : na);
+            nb = nb < 0 ? nb + gf.ny : (nb >= gf.ny ? nb - gf.ny : nb);
+        }
+        const int i = gf.off + na * gf.ny + nb;
+        acc += (T)(1.0 / (double)jcnt[i]) * r[i];
+    }
+    fc[I] = acc;
+}
+
 // e += P e_c (prolongation, ELL-4).
 template <typename T, typename M>
 __global__ void k_prolong_add(int n, const int* __restrict__ pc, const M* __restrict__ pv,
@@ -298,57 +329,48 @@ __global__ void k_interp(int n, int R, FastDiv divR, const int* __restrict__ pc,
 }
 
 // ---------------------------------------------------------------- TV weights
-// Stage 1, per chain (blockIdx.y) and row chunk of seg_rows (blockIdx.x): partial
-// sums of (B x_k)_i^2 and (x_k)_i^2 for the chain's columns k of X = [U | V]
-// (U: Ru columns, ld Ru; V: nv_c columns, ld VS; V unused when use_v == 0),
-// eight columns per pass.  part: [chain][chunk][2 * WS].
-#define COL_CHUNK 8
+// Stage 1, per chain (blockIdx.y) and row chunk of seg_rows (blockIdx.x):
+// partial sums of (B x_k)_i^2 and (x_k)_i^2 for the chain's columns k of
+// X = [U | V] (U: Ru columns, ld Ru; V: nv_c columns, ld VS; V unused when
+// use_v == 0).  Thread layout as in the sweep: R = Ru + nv_c slots per row,
+// BAMG_BLK / R rows per pass (thread t: row t / R, column t % R); each
+// thread keeps its own column's sums, then one thread per column adds them
+// in thread order.  part: [chain][chunk][2 * WS].
 template <typename T, typename M>
 __global__ void __launch_bounds__(BAMG_BLK)
 k_colnorm_partial(const ChainGeo* __restrict__ geo, int seg_rows, int Ru, int use_v, const int* __restrict__ nvc,
                   int VS, const int* __restrict__ rp, const int* __restrict__ ci, const M* __restrict__ v,
                   const T* __restrict__ U, const T* __restrict__ V, int WS, double* __restrict__ part) {
-    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    __shared__ double sr[BAMG_BLK], sx[BAMG_BLK];
     const int c = blockIdx.y;
     const ChainGeo g = geo[c];
     const int R = Ru + (use_v ? nvc[c] : 0);
     const int r0 = g.off + blockIdx.x * seg_rows, r1 = min(g.off + g.n, r0 + seg_rows);
     if (r0 >= r1) return;                 // beyond this chain's own chunks
-    double* out = part + ((size_t)c * gridDim.x + blockIdx.x) * 2 * WS;
-    for (int k0 = 0; k0 < R; k0 += COL_CHUNK) {
-        double sr[COL_CHUNK], sx[COL_CHUNK];
-#pragma unroll
-        for (int q = 0; q < COL_CHUNK; ++q) { sr[q] = 0; sx[q] = 0; }
-        for (int i = r0 + threadIdx.x; i < r1; i += BAMG_BLK) {
-            double acc[COL_CHUNK], xi[COL_CHUNK];
-#pragma unroll
-            for (int q = 0; q < COL_CHUNK; ++q) { acc[q] = 0; xi[q] = 0; }
-            for (int p = rp[i]; p < rp[i + 1]; ++p) {
-                const int j = ci[p];
-                const double b = (double)v[p];
-#pragma unroll
-                for (int q = 0; q < COL_CHUNK; ++q) {
-                    const int k = k0 + q;
-                    if (k < R) {
-                        const double x = k < Ru ? (double)U[(size_t)j * Ru + k] : (double)V[(size_t)j * VS + (k - Ru)];
-                        acc[q] += b * x;
-                    }
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < COL_CHUNK; ++q) {
-                const int k = k0 + q;
-                if (k < R) xi[q] = k < Ru ? (double)U[(size_t)i * Ru + k] : (double)V[(size_t)i * VS + (k - Ru)];
-                sr[q] += acc[q] * acc[q];
-                sx[q] += xi[q] * xi[q];
-            }
+    const int t = threadIdx.x, rpp = BAMG_BLK / R, dr = t / R, k = t - dr * R;
+    const bool inU = k < Ru;
+    const T* __restrict__ X = inU ? U : V;
+    const int ld = inU ? Ru : VS, kx = inU ? k : k - Ru;
+    double ar = 0, ax = 0;
+    if (dr < rpp) {
+        for (int i = r0 + dr; i < r1; i += rpp) {
+            double acc = 0;
+            const int p1 = rp[i + 1];
+            for (int p = rp[i]; p < p1; ++p) acc += (double)v[p] * (double)X[(size_t)ci[p] * ld + kx];
+            const double xi = (double)X[(size_t)i * ld + kx];
+            ar += acc * acc;
+            ax += xi * xi;
         }
-#pragma unroll
-        for (int q = 0; q < COL_CHUNK; ++q) {
-            double a = block_sum(sr[q], sh);
-            double b = block_sum(sx[q], sh);
-            if (threadIdx.x == 0 && k0 + q < R) { out[k0 + q] = a; out[WS + k0 + q] = b; }
-        }
+    }
+    sr[t] = ar;
+    sx[t] = ax;
+    __syncthreads();
+    if (t < R) {
+        double a = 0, b = 0;
+        for (int q = t; q < rpp * R; q += R) { a += sr[q]; b += sx[q]; }
+        double* out = part + ((size_t)c * gridDim.x + blockIdx.x) * 2 * WS;
+        out[t] = a;
+        out[WS + t] = b;
     }
 }
 
@@ -427,11 +449,13 @@ __device__ __forceinline__ bool chol4(const double G[4][4], const double b[4], i
 // (strict minimum, ties to the lower slot) until |J| >= caliber; a candidate
 // g is admissible when det(G_{J+g}) / det(G_J) > 1e-10 G_gg (its Schur
 // complement pivot).  Gram and solves in FP64 whatever the storage type.
+// jcnt (optional): |J_i| per fine point, for the restriction of the cycle.
 template <typename T, typename MP>
 __global__ void __launch_bounds__(BAMG_BLK)
 k_ls_fit(int n, const ChainGeo* __restrict__ geo, int nch, int Ru, int use_v, const int* __restrict__ nvc,
          int VS, const T* __restrict__ U, const T* __restrict__ V, const double* __restrict__ wall, int WS,
-         int caliber, int* __restrict__ pc, MP* __restrict__ pv, T* __restrict__ inject, int* __restrict__ jmask) {
+         int caliber, int* __restrict__ pc, MP* __restrict__ pv, T* __restrict__ inject,
+         unsigned char* __restrict__ jcnt) {
     int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
     if (i >= n) return;
     const int ch = find_chain(geo, nch, i);
@@ -448,7 +472,7 @@ k_ls_fit(int n, const ChainGeo* __restrict__ geo, int nch, int Ru, int use_v, co
         for (int s = 1; s < 4; ++s) { pc[(size_t)i * 4 + s] = -1; pv[(size_t)i * 4 + s] = (MP)0; }
         if (inject)
             for (int k = 0; k < Ru; ++k) inject[(size_t)I * Ru + k] = U[(size_t)i * Ru + k];
-        if (jmask) jmask[i] = 0;
+        if (jcnt) jcnt[i] = 1;
         return;
     }
     // neighbourhood slots
@@ -570,16 +594,18 @@ k_ls_fit(int n, const ChainGeo* __restrict__ geo, int nch, int Ru, int use_v, co
         pv[(size_t)i * 4 + rank] = (MP)p[s];
     }
     for (int s = cnt; s < 4; ++s) { pc[(size_t)i * 4 + s] = -1; pv[(size_t)i * 4 + s] = (MP)0; }
-    if (jmask) jmask[i] = J;
+    if (jcnt) jcnt[i] = (unsigned char)cnt;
 }
 
 // ---------------------------------------------------------------- Q
 // Averaging restriction (Section 4): Q[I, i] = 1/|J_i| for every fine i with
 // I in J_i.  Such i lie in the 3x3 fine box around I's fine position; they
-// are written in ascending fine index.
+// are written in ascending fine index (ELL-9, for the Galerkin products), and
+// qmask[I] marks which box slots (da, db) = (s / 3 - 1, s % 3 - 1) they are.
 template <typename MQ>
 __global__ void k_build_q(int nc, const ChainGeo* __restrict__ geoc, const ChainGeo* __restrict__ geof, int nch,
-                          const int* __restrict__ pc, int* __restrict__ qc, MQ* __restrict__ qv) {
+                          const int* __restrict__ pc, int* __restrict__ qc, MQ* __restrict__ qv,
+                          unsigned short* __restrict__ qmask) {
     int I = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
     if (I >= nc) return;
     const int ch = find_chain(geoc, nch, I);
@@ -625,6 +651,10 @@ __global__ void k_build_q(int nc, const ChainGeo* __restrict__ geoc, const Chain
         qv[(size_t)I * 9 + rank] = (MQ)fv[s];
     }
     for (int s = cnt; s < 9; ++s) { qc[(size_t)I * 9 + s] = -1; qv[(size_t)I * 9 + s] = (MQ)0; }
+    unsigned m = 0;
+#pragma unroll
+    for (int s = 0; s < 9; ++s) m |= (fi[s] >= 0 ? 1u : 0u) << s;
+    qmask[I] = (unsigned short)m;
 }
 
 // ---------------------------------------------------------------- Galerkin
@@ -769,96 +799,100 @@ k_galerkin_numeric(int nc, const ChainGeo* __restrict__ geoc, int nch,
 
 // ---------------------------------------------------------------- up-leg
 // One omega-Jacobi sweep on (B - lam_c T) x_c = 0 for every column c of the
-// eigenvector block V (R columns, row-major).  kind[c]: 0 real column with
-// real lam, 1/2 real/imaginary part of a complex pair (x = V_c + i V_{c+1},
-// lam complex); D_lam = diag(B) - lam diag(T).  T == identity when trp is
-// null.  Column 0 (the null-vector approximation) has lam = 0.
+// eigenvector block V (row stride R), one thread per (row, column) with the
+// chain's first nvc columns in use.  kind[c]: 0 real column with real lam,
+// 1 / 2 real / imaginary part of a complex pair x = V_c + i V_{c+1} (lam
+// complex; both columns of a pair form (B - lam T) x, each keeps its own
+// part); D_lam = diag(B) - lam diag(T).  T == identity when trp is null.
+// Column 0 (the null-vector approximation) has lam = 0.
 template <typename T, typename M>
 __global__ void __launch_bounds__(BAMG_BLK)
-k_eig_relax(int n, const ChainGeo* __restrict__ geo, int nch, int R, const int* __restrict__ nvc, int KV,
-            const int* __restrict__ brp, const int* __restrict__ bci, const M* __restrict__ bv,
+k_eig_relax(int n, const ChainGeo* __restrict__ geo, int nch, int R, FastDiv divR, const int* __restrict__ nvc,
+            int KV, const int* __restrict__ brp, const int* __restrict__ bci, const M* __restrict__ bv,
             const int* __restrict__ trp, const int* __restrict__ tci, const M* __restrict__ tv,
             const double* __restrict__ lamall, const int* __restrict__ kindall, double omega,
             const T* __restrict__ X, T* __restrict__ Y) {
-    int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
-    if (i >= n) return;
-    // R: row stride of X / Y; the chain uses its first nvc columns
+    const long long tt = (long long)xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (tt >= (long long)n * R) return;
+    const int i = (int)divR.div((uint32_t)tt), c = (int)(tt - (long long)i * R);
     const int ch = find_chain(geo, nch, i);
-    const int nv = nvc[ch];
-    const double* __restrict__ lam = lamall + (size_t)ch * 2 * KV;
-    const int* __restrict__ kind = kindall + (size_t)ch * KV;
-    double bx[10], tx[10], bd = 0, td = trp ? 0.0 : 1.0;
-    for (int c = 0; c < nv; ++c) { bx[c] = 0; tx[c] = trp ? 0.0 : (double)X[(size_t)i * R + c]; }
+    if (c >= nvc[ch]) return;
+    const int k = kindall[(size_t)ch * KV + c];
+    const double lr = lamall[(size_t)ch * 2 * KV + 2 * c], li = lamall[(size_t)ch * 2 * KV + 2 * c + 1];
+    const int ca = k == 2 ? c - 1 : c;            // real-part column of the pair
+    const bool pair = k != 0;
+    double b0 = 0, b1 = 0, t0 = 0, t1 = 0, bd = 0, td = trp ? 0.0 : 1.0;
     for (int p = brp[i]; p < brp[i + 1]; ++p) {
-        int j = bci[p];
-        double b = (double)bv[p];
+        const int j = bci[p];
+        const double b = (double)bv[p];
         if (j == i) bd = b;
-        for (int c = 0; c < nv; ++c) bx[c] += b * (double)X[(size_t)j * R + c];
+        b0 += b * (double)X[(size_t)j * R + ca];
+        if (pair) b1 += b * (double)X[(size_t)j * R + ca + 1];
     }
-    if (trp)
+    if (trp) {
         for (int p = trp[i]; p < trp[i + 1]; ++p) {
-            int j = tci[p];
-            double t = (double)tv[p];
+            const int j = tci[p];
+            const double t = (double)tv[p];
             if (j == i) td = t;
-            for (int c = 0; c < nv; ++c) tx[c] += t * (double)X[(size_t)j * R + c];
+            t0 += t * (double)X[(size_t)j * R + ca];
+            if (pair) t1 += t * (double)X[(size_t)j * R + ca + 1];
         }
-    for (int c = 0; c < nv; ++c) {
-        int k = kind[c];
-        double lr = lam[2 * c], li = lam[2 * c + 1];
-        if (k == 0) {
-            double res = bx[c] - lr * tx[c];
-            double d = bd - lr * td;
-            Y[(size_t)i * R + c] = (T)((double)X[(size_t)i * R + c] - omega * res / d);
-        } else if (k == 1) {
-            // x = a + i b, r = (B - lam T) x, D = bd - lam td
-            double rr = (bx[c] - lr * tx[c]) + li * tx[c + 1];
-            double ri = (bx[c + 1] - lr * tx[c + 1]) - li * tx[c];
-            double dr = bd - lr * td, di = -li * td;
-            double den = dr * dr + di * di;
-            double qr = (rr * dr + ri * di) / den, qi = (ri * dr - rr * di) / den;
-            Y[(size_t)i * R + c] = (T)((double)X[(size_t)i * R + c] - omega * qr);
-            Y[(size_t)i * R + c + 1] = (T)((double)X[(size_t)i * R + c + 1] - omega * qi);
-            ++c;
-        }
+    } else {
+        t0 = (double)X[(size_t)i * R + ca];
+        if (pair) t1 = (double)X[(size_t)i * R + ca + 1];
+    }
+    const double xo = (double)X[(size_t)i * R + c];
+    if (!pair) {
+        Y[(size_t)i * R + c] = (T)(xo - omega * (b0 - lr * t0) / (bd - lr * td));
+    } else {
+        // r = (B - lam T) x, D = bd - lam td, correction r / D
+        const double rr = (b0 - lr * t0) + li * t1;
+        const double ri = (b1 - lr * t1) - li * t0;
+        const double dr = bd - lr * td, di = -li * td;
+        const double den = dr * dr + di * di;
+        const double q = k == 1 ? (rr * dr + ri * di) / den : (ri * dr - rr * di) / den;
+        Y[(size_t)i * R + c] = (T)(xo - omega * q);
     }
 }
 
 // Rayleigh quotient partials, per chain (blockIdx.y) and row chunk of
-// seg_rows (blockIdx.x): for entry e (first column ent_col[e]; a pair uses two) the
-// sums x^H B x and x^H T x (re, im) -> part[chain][chunk][entry][4].
+// seg_rows (blockIdx.x): for entry e (first column ent_col[e]; a pair uses
+// two) the sums x^H B x and x^H T x (re, im).  Thread layout: nent slots per
+// row (thread t: row t / nent, entry t % nent), then one thread per entry adds
+// the per-thread sums in thread order -> part[chain][chunk][entry][4].
 template <typename T, typename M>
-__global__ void k_rayleigh_partial(const ChainGeo* __restrict__ geo, int R, int KV, const int* __restrict__ nentc,
-                                   const int* __restrict__ ent_colall, const int* __restrict__ kindall,
-                                   const int* __restrict__ brp, const int* __restrict__ bci, const M* __restrict__ bv,
-                                   const int* __restrict__ trp, const int* __restrict__ tci, const M* __restrict__ tv,
-                                   const T* __restrict__ X, int seg_rows, double* __restrict__ part) {
-    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+__global__ void __launch_bounds__(BAMG_BLK)
+k_rayleigh_partial(const ChainGeo* __restrict__ geo, int R, int KV, const int* __restrict__ nentc,
+                   const int* __restrict__ ent_colall, const int* __restrict__ kindall,
+                   const int* __restrict__ brp, const int* __restrict__ bci, const M* __restrict__ bv,
+                   const int* __restrict__ trp, const int* __restrict__ tci, const M* __restrict__ tv,
+                   const T* __restrict__ X, int seg_rows, double* __restrict__ part) {
+    __shared__ double sh[4][BAMG_BLK];
     const int chn = blockIdx.y;
     const ChainGeo g = geo[chn];
     const int nent = nentc[chn];
-    const int* ent_col = ent_colall + (size_t)chn * KV;
-    const int* kind = kindall + (size_t)chn * KV;
     const int r0 = g.off + blockIdx.x * seg_rows, r1 = min(g.off + g.n, r0 + seg_rows);
     if (r0 >= r1) return;
-    for (int e = 0; e < nent; ++e) {
-        int c = ent_col[e];
-        bool pair = kind[c] == 1;
-        double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-        for (int i = r0 + threadIdx.x; i < r1; i += BAMG_BLK) {
-            double xr = (double)X[(size_t)i * R + c], xi = pair ? (double)X[(size_t)i * R + c + 1] : 0.0;
+    const int t = threadIdx.x, rpp = BAMG_BLK / nent, dr = t / nent, e = t - dr * nent;
+    const int c = ent_colall[(size_t)chn * KV + e];
+    const bool pair = kindall[(size_t)chn * KV + c] == 1;
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    if (dr < rpp) {
+        for (int i = r0 + dr; i < r1; i += rpp) {
+            const double xr = (double)X[(size_t)i * R + c], xi = pair ? (double)X[(size_t)i * R + c + 1] : 0.0;
             double br = 0, bi = 0, tr = 0, ti = 0;
             for (int p = brp[i]; p < brp[i + 1]; ++p) {
-                int j = bci[p];
-                double b = (double)bv[p];
+                const int j = bci[p];
+                const double b = (double)bv[p];
                 br += b * (double)X[(size_t)j * R + c];
                 if (pair) bi += b * (double)X[(size_t)j * R + c + 1];
             }
             if (trp) {
                 for (int p = trp[i]; p < trp[i + 1]; ++p) {
-                    int j = tci[p];
-                    double t = (double)tv[p];
-                    tr += t * (double)X[(size_t)j * R + c];
-                    if (pair) ti += t * (double)X[(size_t)j * R + c + 1];
+                    const int j = tci[p];
+                    const double tq = (double)tv[p];
+                    tr += tq * (double)X[(size_t)j * R + c];
+                    if (pair) ti += tq * (double)X[(size_t)j * R + c + 1];
                 }
             } else {
                 tr = xr; ti = xi;
@@ -867,11 +901,15 @@ __global__ void k_rayleigh_partial(const ChainGeo* __restrict__ geo, int R, int 
             s0 += xr * br + xi * bi; s1 += xr * bi - xi * br;
             s2 += xr * tr + xi * ti; s3 += xr * ti - xi * tr;
         }
-        s0 = block_sum(s0, sh); s1 = block_sum(s1, sh); s2 = block_sum(s2, sh); s3 = block_sum(s3, sh);
-        if (threadIdx.x == 0) {
-            double* o = part + (((size_t)chn * gridDim.x + blockIdx.x) * KV + e) * 4;
-            o[0] = s0; o[1] = s1; o[2] = s2; o[3] = s3;
-        }
+    }
+    sh[0][t] = s0; sh[1][t] = s1; sh[2][t] = s2; sh[3][t] = s3;
+    __syncthreads();
+    if (t < nent) {
+        double a[4] = {0, 0, 0, 0};
+        for (int q = t; q < rpp * nent; q += nent)
+            for (int z = 0; z < 4; ++z) a[z] += sh[z][q];
+        double* o = part + (((size_t)chn * gridDim.x + blockIdx.x) * KV + t) * 4;
+        for (int z = 0; z < 4; ++z) o[z] = a[z];
     }
 }
 

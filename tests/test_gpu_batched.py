@@ -210,3 +210,18 @@ def test_batched_vcycle_is_per_chain_vcycle():
         want = e1.cpu().numpy()
         assert np.abs(eb[c] - want).max() <= 1e-14 * np.abs(want).max(), c
         h1.close()
+
+
+def test_trim_returns_cached_memory_and_handles_still_work():
+    ch = C.tandem_queue(32)
+    h = B.Hierarchy.from_chain(ch, R, B.default_options(levels=3))
+    h2 = B.Hierarchy.from_chain(ch, R, B.default_options(levels=3))
+    h2.close()
+    B.trim()                             # h2's buffers go back to HIP, h keeps its own
+    x = torch.empty(ch.n, dtype=torch.float64, device="cuda")
+    info = h.solve(x, 1e-12, 100)
+    assert info.converged
+    h3 = B.Hierarchy.from_chain(ch, R, B.default_options(levels=3))
+    x3 = torch.empty(ch.n, dtype=torch.float64, device="cuda")
+    h3.solve(x3, 1e-12, 100)
+    assert torch.equal(x, x3)
