@@ -99,9 +99,10 @@ def _roofline(stats, traffic):
     sweep_ms = sum(s.sweep_ms for s in stats) / max(1, sum(s.sweep_launches for s in stats))
     sweep_bytes = stats[-1].sweep_bytes
     achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9
+    st = stats[-1]
     return sweep_ms, {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                       "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                      "kernel": "k_sweep (level-0 test-vector sweep)",
+                      "kernel": "k_sweep_v<VW=%d,BS=%d> (level-0 test-vector sweep)" % (st.sweep_vw, st.sweep_bs),
                       "bytes_per_launch": int(sweep_bytes), "mean_launch_us": round(sweep_ms * 1e3, 2)}
 
 
@@ -117,6 +118,8 @@ def _kernel_detail(stats):
         "lsfit_us": round(ls_ms * 1e3, 2),
         "lsfit_GBps": round(stats[-1].lsfit_bytes / (ls_ms * 1e-3) / 1e9, 1) if ls_ms > 0 else None,
         "coarsest_min_pivot": stats[-1].coarsest_min_pivot,
+        "cycle_graph": stats[-1].cycle_graph,
+        "sweep_tune_ms_total": round(stats[-1].tune_ms, 2),
     }
 
 
@@ -147,6 +150,9 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
                     help="default: fp64 for tandem, mixed for batch64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run three plain device copies of MIB MiB (the reference kernel whose FETCH_SIZE / "
+                         "WRITE_SIZE counters scale the traffic figures) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is described "
@@ -156,6 +162,14 @@ def main():
         args.precision = "fp64" if args.workload == "tandem" else "mixed"
 
     import torch
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": src.numel() * 8, "copies": 3}))
+        return
     from paper_1004_1451_amd import bamg as B
     from paper_1004_1451_amd import chains as C
 

@@ -123,6 +123,11 @@ typedef struct {
     int32_t cycle_graph;    /* 1: cycles replay a captured graph              */
     double cycle_host_us, cycle_gpu_us; /* first cycle (cycle_mode 0): host launch
                                            time and GPU time                 */
+    int32_t sweep_vw, sweep_bs; /* launch shape of the level-0 multi-vector sweep:
+                                   columns per thread, threads per workgroup
+                                   (autotuned once per shape and process;
+                                   BAMG_SWEEP_VARIANT="VW,BS" forces one)    */
+    double tune_ms;         /* process total spent timing sweep candidates    */
 } bamg_stats;
 
 typedef struct {

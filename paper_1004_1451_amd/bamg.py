@@ -64,7 +64,8 @@ class Stats(C.Structure):
                 ("sweep_ms", C.c_double), ("galerkin_ms", C.c_double), ("lsfit_ms", C.c_double),
                 ("sweep_launches", C.c_int32), ("galerkin_launches", C.c_int32), ("lsfit_launches", C.c_int32),
                 ("sweep_bytes", C.c_int64), ("galerkin_bytes", C.c_int64), ("lsfit_bytes", C.c_int64),
-                ("cycle_graph", C.c_int32), ("cycle_host_us", C.c_double), ("cycle_gpu_us", C.c_double)]
+                ("cycle_graph", C.c_int32), ("cycle_host_us", C.c_double), ("cycle_gpu_us", C.c_double),
+                ("sweep_vw", C.c_int32), ("sweep_bs", C.c_int32), ("tune_ms", C.c_double)]
 
 
 class LevelInfo(C.Structure):

@@ -20,6 +20,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <numeric>
 #include <stdexcept>
@@ -168,6 +169,35 @@ struct DeviceCache {
 DeviceCache& device_cache() {
     static DeviceCache* c = new DeviceCache();        // lives until the process ends
     return *c;
+}
+
+// Autotuned launch shape of the multi-vector sweep: a thread owns VW adjacent
+// columns of a row, workgroups of BS threads.  Every variant computes the same
+// bits; the fastest for a (device, rows, R, nnz, type) shape is found once per
+// process by timing each candidate on the real operator, then reused.
+// BAMG_SWEEP_VARIANT="VW,BS" in the environment forces a variant.
+struct SweepShape { int vw = 1, bs = 256; };
+
+struct SweepTuner {
+    std::mutex mu;
+    std::map<std::tuple<int, int, int, int, int>, SweepShape> best;
+    double tune_ms = 0;
+};
+
+SweepTuner& sweep_tuner() {
+    static SweepTuner* t = new SweepTuner();
+    return *t;
+}
+
+bool forced_sweep_shape(int R, SweepShape& out) {
+    const char* e = getenv("BAMG_SWEEP_VARIANT");
+    if (!e || !*e) return false;
+    int vw = 0, bs = 0;
+    if (sscanf(e, "%d,%d", &vw, &bs) != 2) return false;
+    if ((vw != 1 && vw != 2 && vw != 4) || (bs != 128 && bs != 256 && bs != 512) || R % vw) return false;
+    out.vw = vw;
+    out.bs = bs;
+    return true;
 }
 
 struct Arena {
@@ -582,19 +612,92 @@ struct Engine : bamg_ctx {
 
     // -------------------------------------------------------------- setup steps
     // nu homogeneous sweeps on the continuing rows of level l (R columns).
+    template <int VW, int BS>
+    void sweep_launch(int rows, int R, const Csr<T>& Bm, const T* dinv, const T* X, const T* F, T* Y) {
+        const int G = R / VW;
+        const long long tot = (long long)rows * G;
+        const int grid = (int)std::max<long long>(1, (tot + BS - 1) / BS);
+        hipLaunchKernelGGL((k_sweep_v<T, T, VW, BS>), dim3(grid), dim3(BS), 0, s, rows, G, FastDiv((uint32_t)G),
+                           (const int*)Bm.rp, (const int*)Bm.ci, (const T*)Bm.v, dinv, X, F, Y);
+        HIPCHK(hipGetLastError());
+    }
+
+    void sweep_shape(const SweepShape& sh, int rows, int R, const Csr<T>& Bm, const T* dinv, const T* X, const T* F,
+                     T* Y) {
+        switch (sh.vw * 1000 + sh.bs) {
+            case 1128: sweep_launch<1, 128>(rows, R, Bm, dinv, X, F, Y); break;
+            case 1256: sweep_launch<1, 256>(rows, R, Bm, dinv, X, F, Y); break;
+            case 1512: sweep_launch<1, 512>(rows, R, Bm, dinv, X, F, Y); break;
+            case 2128: sweep_launch<2, 128>(rows, R, Bm, dinv, X, F, Y); break;
+            case 2256: sweep_launch<2, 256>(rows, R, Bm, dinv, X, F, Y); break;
+            case 2512: sweep_launch<2, 512>(rows, R, Bm, dinv, X, F, Y); break;
+            case 4128: sweep_launch<4, 128>(rows, R, Bm, dinv, X, F, Y); break;
+            case 4256: sweep_launch<4, 256>(rows, R, Bm, dinv, X, F, Y); break;
+            case 4512: sweep_launch<4, 512>(rows, R, Bm, dinv, X, F, Y); break;
+            default: fail(BAMG_EDEVICE, "no sweep variant %d,%d", sh.vw, sh.bs);
+        }
+    }
+
+    // Launch shape for a sweep of this level: forced, cached, or tuned now by
+    // timing every candidate once (X -> scratch, X unchanged).  Shapes below
+    // 2^20 entries are not worth timing and take the plain layout.
+    SweepShape pick_sweep_shape(int l, int R, const T* X, T* scratch) {
+        SweepShape sh;
+        if (forced_sweep_shape(R, sh)) return sh;
+        auto& lv = L[l];
+        const int rows = lv.cont_rows;
+        if ((long long)rows * R < (1LL << 20)) return sh;
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        const int nnz = get1(lv.B.rp + rows);
+        auto key = std::make_tuple(dev, rows, R, nnz, (int)sizeof(T));
+        auto& tu = sweep_tuner();
+        {
+            std::lock_guard<std::mutex> lk(tu.mu);
+            auto it = tu.best.find(key);
+            if (it != tu.best.end()) return it->second;
+        }
+        auto t0 = std::chrono::steady_clock::now();
+        std::vector<SweepShape> cand;
+        for (int vw : {1, 2, 4})
+            for (int bs : {128, 256, 512})
+                if (R % vw == 0) cand.push_back({vw, bs});
+        hipEvent_t a, b;
+        HIPCHK(hipEventCreate(&a));
+        HIPCHK(hipEventCreate(&b));
+        sweep_shape(cand[0], rows, R, lv.B, lv.dinv, X, nullptr, scratch);     // warm-up
+        float bestms = 1e30f;
+        for (auto& c : cand) {
+            HIPCHK(hipEventRecord(a, s));
+            sweep_shape(c, rows, R, lv.B, lv.dinv, X, nullptr, scratch);
+            HIPCHK(hipEventRecord(b, s));
+            HIPCHK(hipEventSynchronize(b));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, a, b));
+            if (ms < bestms) { bestms = ms; sh = c; }
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        std::lock_guard<std::mutex> lk(tu.mu);
+        tu.best[key] = sh;
+        tu.tune_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return sh;
+    }
+
+    // nu homogeneous sweeps on the continuing rows of level l (R columns).
     void sweeps(int l, T* X, int R, int nu, bool profile) {
         auto& lv = L[l];
         const int rows = lv.cont_rows;
         if (rows == 0 || nu == 0) return;
         T* a = X;
         T* b = sweep_tmp;
-        FastDiv dR((uint32_t)R);
+        const SweepShape sh = pick_sweep_shape(l, R, X, sweep_tmp);
+        if (l == 0) { st.sweep_vw = sh.vw; st.sweep_bs = sh.bs; }
         long long tot = (long long)rows * R;
         for (int k = 0; k < nu; ++k) {
             std::pair<hipEvent_t, hipEvent_t> ev;
             if (profile) ev = ev_begin();
-            LAUNCH((k_sweep<T, T>), nblk(tot), BAMG_BLK, s, rows, R, dR, lv.B.rp, lv.B.ci, (const T*)lv.B.v,
-                   (const T*)lv.dinv, (const T*)a, (const T*)nullptr, b);
+            sweep_shape(sh, rows, R, lv.B, lv.dinv, a, nullptr, b);
             if (profile) ev_end(ev, ev_sweep);
             std::swap(a, b);
         }
@@ -943,6 +1046,7 @@ struct Engine : bamg_ctx {
             v.clear();
         };
         acc(ev_sweep, st.sweep_ms, st.sweep_launches);
+        st.tune_ms = sweep_tuner().tune_ms;
         acc(ev_gal, st.galerkin_ms, st.galerkin_launches);
         acc(ev_ls, st.lsfit_ms, st.lsfit_launches);
         // algorithmic bytes of one level-0 launch

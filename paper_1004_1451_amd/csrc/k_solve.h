@@ -268,12 +268,24 @@ k_seg_mdot_partial(const ChainGeo* __restrict__ geo, int seg_rows, int N, int nb
     const int i0 = g.off + blockIdx.x * seg_rows, i1 = min(g.off + g.n, i0 + seg_rows);
     if (i0 >= i1) return;
     const size_t slot = (((size_t)blockIdx.y * gridDim.x + blockIdx.x) * (BAMG_BLK / BAMG_WAVE) + wv) * nv;
-    for (int b = 0; b < nv; ++b) {
-        const double* vb = b < nb ? V + (size_t)b * N : w;
-        double s = 0;
-        for (int i = i0 + threadIdx.x; i < i1; i += BAMG_BLK) s += vb[i] * w[i];
-        s = wave_sum(s);
-        if (lane == 0) part[slot + b] = s;
+    // eight dots per pass over the chunk: w is read once per eight vectors
+    for (int b0 = 0; b0 < nv; b0 += 8) {
+        double s[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s[q] = 0;
+        for (int i = i0 + threadIdx.x; i < i1; i += BAMG_BLK) {
+            const double wi = w[i];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int b = b0 + q;
+                if (b < nv) s[q] += (b < nb ? V[(size_t)b * N + i] : wi) * wi;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const double t = wave_sum(s[q]);
+            if (lane == 0 && b0 + q < nv) part[slot + b0 + q] = t;
+        }
     }
 }
 

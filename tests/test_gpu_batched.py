@@ -225,3 +225,17 @@ def test_trim_returns_cached_memory_and_handles_still_work():
     x3 = torch.empty(ch.n, dtype=torch.float64, device="cuda")
     h3.solve(x3, 1e-12, 100)
     assert torch.equal(x, x3)
+
+
+@pytest.mark.parametrize("variant", ["1,128", "2,256", "4,512", "4,256"])
+def test_sweep_variants_give_the_same_bits(variant, monkeypatch):
+    # every launch shape the autotuner may pick computes the same numbers
+    ch = C.tandem_queue(40)
+    opts = B.default_options(levels=3, stop_after=1)
+    monkeypatch.setenv("BAMG_SWEEP_VARIANT", "1,256")
+    ref = B.Hierarchy.from_chain(ch, 12, opts).export(0, B.X_U)
+    monkeypatch.setenv("BAMG_SWEEP_VARIANT", variant)
+    h = B.Hierarchy.from_chain(ch, 12, opts)
+    assert np.array_equal(h.export(0, B.X_U), ref)
+    vw, bs = map(int, variant.split(","))
+    assert (h.stats().sweep_vw, h.stats().sweep_bs) == (vw, bs)
