@@ -25,11 +25,12 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 
 
-def _traffic_from_profiles(kernel: str):
+def _traffic_from_profiles(name: str):
     """HBM bytes per launch measured by rocprofv3 counters, if a summary for
-    this kernel is committed (profiles/<kernel>_traffic.txt: a line
-    'bytes_per_launch: <value>' and 'source_hash: <sha>'), else None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.txt")
+    this kernel and workload is committed (profiles/<name>_traffic.txt with
+    lines 'bytes_per_launch: <value>' and 'source_hash: <sha>'), else None.
+    None too when the kernel source changed after the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{name}_traffic.txt")
     if not os.path.exists(path):
         return None
     import hashlib
@@ -50,22 +51,23 @@ def _traffic_from_profiles(kernel: str):
 
 def cpu_baseline(args):
     """The oracle, untuned, on a bounded sample: the whole method on the
-    tandem queue N = 255 (n = 65,536; 4 levels; same r, rates and tolerance),
-    scaled to n = 4,194,304 by the ratio of state counts (the work per level
-    is linear in n).  BLAS limited to one thread."""
+    tandem queue N = 767 (n = 589,824; the same 6 levels, r, rates and
+    tolerance), scaled to n = 4,194,304 by the ratio of state counts (the
+    work per level is linear in n).  BLAS limited to one thread."""
     from threadpoolctl import threadpool_limits
     from oracle import bamg_oracle as O
     from paper_1004_1451_amd import chains as C
-    ch = C.tandem_queue(255)
+    ch = C.tandem_queue(767)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         x, info, _ = O.stationary(ch.to_scipy(), O.Grid(ch.nx, ch.ny, ch.periodic), args.r,
-                                  O.Options(levels=4), tol=args.tol, max_cycles=200)
+                                  O.Options(levels=args.levels), tol=args.tol, max_cycles=200)
         dt = time.perf_counter() - t0
     scale = 4194304 / ch.n
     return {"value": dt * scale, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle setup+solve on tandem N=255 (n={ch.n}, 4 levels, r={args.r}, tol={args.tol:g}) "
-                      f"took {dt:.2f} s on 1 thread; scaled by n ratio {scale:.0f}",
+            "sample": f"oracle setup+solve on tandem N=767 (n={ch.n:,}, {args.levels} levels, r={args.r}, "
+                      f"tol={args.tol:g}, {info.cycles} cycles) took {dt:.2f} s on 1 thread; scaled by n ratio "
+                      f"{scale:.2f}",
             "converged": bool(info.converged)}
 
 
@@ -147,8 +149,11 @@ def main():
     ap.add_argument("--levels", type=int, default=6)
     ap.add_argument("--r", type=int, default=12)
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
-                    help="default: fp64 for tandem, mixed for batch64")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed",
+                    help="mixed (default): FP32 relaxation, Galerkin products and cycle, FP64 coarsest level, norms "
+                         "and outer iteration; fp64: every step in FP64")
+    ap.add_argument("--no-fp64-compare", action="store_true",
+                    help="skip the untimed FP64 run that the mixed result is compared with")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run three plain device copies of MIB MiB (the reference kernel whose FETCH_SIZE / "
@@ -158,8 +163,6 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is described "
               f"in DESIGN.md and not built", file=sys.stderr)
         sys.exit(2)
-    if args.precision is None:
-        args.precision = "fp64" if args.workload == "tandem" else "mixed"
 
     import torch
     if args.calibrate_copy:
@@ -174,7 +177,7 @@ def main():
     from paper_1004_1451_amd import chains as C
 
     prec = B.FP64 if args.precision == "fp64" else B.MIXED
-    traffic = _traffic_from_profiles("k_sweep")
+    traffic = _traffic_from_profiles(f"k_sweep_v_{args.workload}_{args.precision}")
     if args.workload == "tandem":
         ch = C.tandem_queue(args.N)
         rp, ci, v = B.device_csr(ch)
@@ -198,6 +201,15 @@ def main():
                        "history": [float("%.3e" % v) for v in list(infos[-1].history)[: infos[-1].history_len]],
                        "residual_l1": max(i.residual_l1 for i in infos),
                        "converged": all(i.converged for i in infos)})
+        if prec == B.MIXED and not args.no_fp64_compare:
+            # outside the timed region: the plain FP64 form, its time per step
+            # and how far the mixed solution is from it
+            x_mixed = x.clone()
+            opts = B.default_options(levels=args.levels, precision=B.FP64, profile=1)
+            sec64, res64 = _timed(step, argparse.Namespace(warmup=1, steps=max(1, min(args.steps, 3))))
+            detail["fp64_ms_per_step"] = round(sec64 * 1e3, 3)
+            detail["fp64_cycles"] = res64[-1][0].cycles
+            detail["l1_diff_vs_fp64_path"] = float((x - x_mixed).abs().sum().item())
         out = {
             "metric": "setup+solve seconds to ||Bx||_1/||x||_1<=1e-10 at n=4.2M; sweep HBM GB/s",
             "value": round(sec, 6), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -224,7 +236,7 @@ def main():
 
         sec, res = _timed(step, args)
         stats = [r[3] for r in res]
-        sweep_ms, roof = _roofline(stats, None)
+        sweep_ms, roof = _roofline(stats, traffic)
         roof["kernel"] += ", R=%d, all 64 chains" % args.r
         detail = _kernel_detail(stats)
         detail.update({"chains_per_s": round(64 / sec, 2), "cycles": [r[0].cycles for r in res],
