@@ -97,6 +97,15 @@ typedef struct {
     int32_t cycle_mode;  /* 0: decide on the first cycle (graph when the cycle
                             is launch-bound); 1: eager launches; 2: HIP graph
                             of one cycle, captured once and replayed          */
+    int32_t setup_passes;/* 2 (0 = default): down-leg, up-leg, then every P, B,
+                            T recomputed from U and V; 1: the first pass only
+                            (the cycle uses the first-pass hierarchy)          */
+    int32_t collect;     /* 1: keep the first-pass features and the final
+                            slot weights of every level for bamg_export
+                            (BAMG_X_FEATURES, BAMG_X_SLOTW): training data    */
+    float mlp_judge;     /* learned form: keep the network's row when the LS
+                            functional at it is <= mlp_judge x the fit's
+                            minimum (default 2)                               */
 } bamg_options;
 
 typedef struct {
@@ -128,6 +137,8 @@ typedef struct {
                                    (autotuned once per shape and process;
                                    BAMG_SWEEP_VARIANT="VW,BS" forces one)    */
     double tune_ms;         /* process total spent timing sweep candidates    */
+    int64_t mlp_points;     /* learned form: F points judged (all levels)      */
+    int64_t mlp_fallback;   /* of which fell back to the least-squares row     */
 } bamg_stats;
 
 typedef struct {
@@ -159,10 +170,15 @@ typedef struct {
 #define BAMG_X_W 14         /* double[n*n] (coarsest level): B_L^+ row-major   */
 #define BAMG_X_Y 15         /* double[n] (coarsest level): null vector, 1^T T y = 1 */
 #define BAMG_X_U0 16        /* double[n*r] level 0: the initial test vectors   */
+#define BAMG_X_FEATURES 17  /* float[n*24] first-pass features of every point
+                               (zero rows for C points); needs options.collect */
+#define BAMG_X_SLOTW 18     /* float[n*4] final interpolation weights in slot
+                               order (lexicographic (da, db)); needs collect  */
 
 /* Fill *opt with the defaults: levels 0, coarse_max 1024, nu_setup 4,
    V(2,2), omega 0.7, caliber 4, n_eig 6, arnoldi_m 64, gmres_m 50,
-   FP64, LS interpolation, seed 0, no budget, no profiling. */
+   FP64, LS interpolation, seed 0, no budget, no profiling, 2 setup passes,
+   mlp_judge 2. */
 void bamg_options_default(bamg_options* opt);
 
 /* Build the hierarchy for A (device CSR, see conventions) with r initial test
@@ -243,6 +259,52 @@ int bamg_export(bamg_handle h, int32_t l, int32_t what, void* dst, size_t bytes)
    (device vectors of n doubles; for a batched handle all chains at once, in
    the caller's concatenated order).  Synchronises the stream. */
 int bamg_apply_vcycle(bamg_handle h, const double* f, double* e);
+
+/* ---- Learned interpolation (the learned form of the first-pass fit) ----
+   A 24-64-64-4 ReLU network maps the 24 features of an F point's
+   least-squares problem (Section 3.2, eq. LSfuncrowi: the slot mask, the
+   operator row -b_ij/b_ii at the 8 neighbour offsets, b_s/G_ss,
+   b_s/sqrt(sigma G_ss), sqrt(G_ss/sigma)) to its 4 slot weights.  Params:
+   BAMG_MLP_NPARAM FP32 values, row-major W1[64][24], b1[64], W2[64][64],
+   b2[64], W3[4][64], b3[4].  Every product runs on the matrix cores with
+   bfloat16 operands (round to nearest even) and FP32 accumulation.  Features
+   and targets are device FP32 arrays, n x 24 and n x 4; the first 4 features
+   (the slot mask) mask the loss.  All calls synchronise the stream. */
+#define BAMG_MLP_NPARAM 6020
+
+typedef struct {
+    int32_t epochs;      /* passes over the training set (default 8)           */
+    int32_t batch;       /* points per Adam step, multiple of 256 (4096)       */
+    float lr, beta1, beta2, eps;   /* Adam (1e-3, 0.9, 0.999, 1e-8)            */
+    uint64_t seed;       /* batch sampling (with replacement); 0 = in order     */
+} bamg_mlp_train_opts;
+
+typedef struct {
+    int32_t steps;
+    double train_loss_first, train_loss_last;   /* batch losses               */
+    double val_loss_first, val_loss_last;       /* before / after training    */
+    double ms;                                  /* wall time of the call      */
+    int32_t val_len;
+    double val_history[64];                     /* after each epoch           */
+} bamg_mlp_train_info;
+
+/* He-uniform weights U(-sqrt(6/fan_in), sqrt(6/fan_in)) from the counter
+   generator, zero biases.  params: device, BAMG_MLP_NPARAM floats. */
+int bamg_mlp_init(uint64_t seed, float* params, void* stream);
+
+/* out[i] = network(feat[i]) for n points (device arrays). */
+int bamg_mlp_forward(const float* feat, int64_t n, const float* params, float* out, void* stream);
+
+/* Masked mean squared error over all n points (one batch) and its gradient
+   (device, BAMG_MLP_NPARAM floats); *loss on the host. */
+int bamg_mlp_loss_grad(const float* feat, const float* tgt, int64_t n, const float* params, float* grad,
+                       double* loss, void* stream);
+
+/* Adam on params (in place) over (feat, tgt); the loss on (vfeat, vtgt),
+   nv >= 0 points, is reported before, after each epoch and at the end.
+   opt and info are host structs (opt NULL = defaults; info may be NULL). */
+int bamg_mlp_train(const float* feat, const float* tgt, int64_t n, const float* vfeat, const float* vtgt, int64_t nv,
+                   float* params, const bamg_mlp_train_opts* opt, bamg_mlp_train_info* info, void* stream);
 
 /* nu omega-Jacobi sweeps X <- X + omega D^-1 (F - B X) on caller data
    (Section 3, eq. amg_relax): B = I - A from device CSR of A (as in

@@ -23,6 +23,8 @@ USE_GUESS = 1
 
 X_B_ROWPTR, X_B_COL, X_B_VAL, X_T_ROWPTR, X_T_COL, X_T_VAL = 1, 2, 3, 4, 5, 6
 X_P_COL, X_P_VAL, X_U, X_V, X_LAMBDA, X_VKIND, X_X0, X_W, X_Y, X_U0 = 7, 8, 9, 10, 11, 12, 13, 14, 15, 16
+X_FEATURES, X_SLOTW = 17, 18
+MLP_NPARAM = 6020
 
 ERROR_NAMES = {EINVAL: "EINVAL", ENOTSTOCH: "ENOTSTOCH", EZERODIAG: "EZERODIAG", EUNSUPPORTED: "EUNSUPPORTED",
                ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOCONV: "ENOCONV", ESINGULAR: "ESINGULAR"}
@@ -30,7 +32,8 @@ ERROR_NAMES = {EINVAL: "EINVAL", ENOTSTOCH: "ENOTSTOCH", EZERODIAG: "EZERODIAG",
 # every symbol include/bamg.h declares
 EXPORTS = ["bamg_options_default", "bamg_setup", "bamg_solve", "bamg_free", "bamg_last_error", "bamg_get_stats",
            "bamg_level_info_get", "bamg_export", "bamg_apply_vcycle", "bamg_relax", "bamg_setup_batched",
-           "bamg_solve_batched", "bamg_trim"]
+           "bamg_solve_batched", "bamg_trim", "bamg_mlp_init", "bamg_mlp_forward", "bamg_mlp_loss_grad",
+           "bamg_mlp_train"]
 
 
 class BamgError(RuntimeError):
@@ -49,7 +52,8 @@ class Options(C.Structure):
                 ("caliber", C.c_int32), ("n_eig", C.c_int32), ("arnoldi_m", C.c_int32),
                 ("gmres_m", C.c_int32), ("precision", C.c_int32), ("interp", C.c_int32),
                 ("mlp_weights", C.c_void_p), ("seed", C.c_uint64), ("mem_budget", C.c_size_t),
-                ("profile", C.c_int32), ("stop_after", C.c_int32), ("cycle_mode", C.c_int32)]
+                ("profile", C.c_int32), ("stop_after", C.c_int32), ("cycle_mode", C.c_int32),
+                ("setup_passes", C.c_int32), ("collect", C.c_int32), ("mlp_judge", C.c_float)]
 
 
 class SolveInfo(C.Structure):
@@ -65,7 +69,19 @@ class Stats(C.Structure):
                 ("sweep_launches", C.c_int32), ("galerkin_launches", C.c_int32), ("lsfit_launches", C.c_int32),
                 ("sweep_bytes", C.c_int64), ("galerkin_bytes", C.c_int64), ("lsfit_bytes", C.c_int64),
                 ("cycle_graph", C.c_int32), ("cycle_host_us", C.c_double), ("cycle_gpu_us", C.c_double),
-                ("sweep_vw", C.c_int32), ("sweep_bs", C.c_int32), ("tune_ms", C.c_double)]
+                ("sweep_vw", C.c_int32), ("sweep_bs", C.c_int32), ("tune_ms", C.c_double),
+                ("mlp_points", C.c_int64), ("mlp_fallback", C.c_int64)]
+
+
+class MlpTrainOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64)]
+
+
+class MlpTrainInfo(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("train_loss_first", C.c_double), ("train_loss_last", C.c_double),
+                ("val_loss_first", C.c_double), ("val_loss_last", C.c_double), ("ms", C.c_double),
+                ("val_len", C.c_int32), ("val_history", C.c_double * 64)]
 
 
 class LevelInfo(C.Structure):
@@ -112,6 +128,14 @@ def load():
     lib.bamg_solve_batched.restype = C.c_int
     lib.bamg_trim.argtypes = []
     lib.bamg_trim.restype = C.c_int
+    lib.bamg_mlp_init.argtypes = [C.c_uint64, vp, vp]
+    lib.bamg_mlp_init.restype = C.c_int
+    lib.bamg_mlp_forward.argtypes = [vp, i64, vp, vp, vp]
+    lib.bamg_mlp_forward.restype = C.c_int
+    lib.bamg_mlp_loss_grad.argtypes = [vp, vp, i64, vp, vp, C.POINTER(C.c_double), vp]
+    lib.bamg_mlp_loss_grad.restype = C.c_int
+    lib.bamg_mlp_train.argtypes = [vp, vp, i64, vp, vp, i64, vp, C.POINTER(MlpTrainOpts), C.POINTER(MlpTrainInfo), vp]
+    lib.bamg_mlp_train.restype = C.c_int
     _lib = lib
     return lib
 
@@ -190,7 +214,7 @@ class Hierarchy:
                  X_P_COL: (4 * n, np.int32), X_P_VAL: (4 * n, np.float64), X_U: (n * li.r, np.float64),
                  X_V: (n * li.n_v, np.float64), X_LAMBDA: (2 * li.n_v, np.float64), X_VKIND: (li.n_v, np.int32),
                  X_X0: (n, np.float64), X_W: (n * n, np.float64), X_Y: (n, np.float64),
-                 X_U0: (n * li.r, np.float64)}
+                 X_U0: (n * li.r, np.float64), X_FEATURES: (n * 24, np.float32), X_SLOTW: (n * 4, np.float32)}
         cnt, dt = sizes[what]
         out = np.empty(int(cnt), dtype=dt)
         _check(load().bamg_export(self._h, int(l), int(what), out.ctypes.data_as(C.c_void_p), out.nbytes))
@@ -267,6 +291,45 @@ class BatchedHierarchy(Hierarchy):
                                        resid.ctypes.data_as(C.c_void_p), C.byref(info))
         _check(rc, allow=(ENOCONV,))
         return info, status, resid
+
+
+def mlp_init(seed, stream=None):
+    """Fresh network parameters (device FP32 tensor of MLP_NPARAM values)."""
+    import torch
+    th = torch.empty(MLP_NPARAM, dtype=torch.float32, device="cuda")
+    _check(load().bamg_mlp_init(int(seed), C.c_void_p(th.data_ptr()), _stream_ptr(stream)))
+    return th
+
+
+def mlp_forward(feat, params, stream=None):
+    import torch
+    n = feat.shape[0]
+    out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    _check(load().bamg_mlp_forward(C.c_void_p(feat.data_ptr()), n, C.c_void_p(params.data_ptr()),
+                                   C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+def mlp_loss_grad(feat, tgt, params, stream=None):
+    import torch
+    g = torch.empty(MLP_NPARAM, dtype=torch.float32, device="cuda")
+    loss = C.c_double()
+    _check(load().bamg_mlp_loss_grad(C.c_void_p(feat.data_ptr()), C.c_void_p(tgt.data_ptr()), feat.shape[0],
+                                     C.c_void_p(params.data_ptr()), C.c_void_p(g.data_ptr()), C.byref(loss),
+                                     _stream_ptr(stream)))
+    return loss.value, g
+
+
+def mlp_train(feat, tgt, params, vfeat=None, vtgt=None, epochs=8, batch=4096, lr=1e-3, seed=6, stream=None):
+    """Adam on params (in place); returns the MlpTrainInfo."""
+    o = MlpTrainOpts(int(epochs), int(batch), float(lr), 0.9, 0.999, 1e-8, int(seed))
+    info = MlpTrainInfo()
+    nv = 0 if vfeat is None else vfeat.shape[0]
+    _check(load().bamg_mlp_train(C.c_void_p(feat.data_ptr()), C.c_void_p(tgt.data_ptr()), feat.shape[0],
+                                 C.c_void_p(vfeat.data_ptr()) if nv else None,
+                                 C.c_void_p(vtgt.data_ptr()) if nv else None, nv, C.c_void_p(params.data_ptr()),
+                                 C.byref(o), C.byref(info), _stream_ptr(stream)))
+    return info
 
 
 def trim():

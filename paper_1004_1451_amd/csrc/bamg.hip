@@ -32,6 +32,7 @@
 #include "common.h"
 #include "k_coarse.h"
 #include "k_dense.h"
+#include "k_learn.h"
 #include "k_solve.h"
 #include "k_sparse.h"
 
@@ -263,6 +264,8 @@ struct Level {
     unsigned short* mask = nullptr;
     unsigned short* qmask = nullptr; // Q's box slots per next-level row (cycle restriction)
     unsigned char* jcnt = nullptr;   // |J_i| per continuing row
+    float* feat = nullptr;           // collected first-pass features (rows x 24)
+    float* slotw = nullptr;          // collected final slot weights (rows x 4)
     int* cnt = nullptr;
     bool zero_into_e2 = false;       // first smoothing sweep target (fixed buffers)
 };
@@ -346,6 +349,11 @@ struct Engine : bamg_ctx {
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_s = nullptr;     // capture needs a stream other than the legacy default one
     bool cycle_decided = false, use_graph = false;
+    // learned form
+    MlpPack* mlp_pk = nullptr;
+    float* learn_part = nullptr;
+    double* learn_acc = nullptr;
+    int learn_grid = 0;
     // profiling
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_sweep, ev_gal, ev_ls;
 
@@ -486,6 +494,10 @@ struct Engine : bamg_ctx {
                 lv.mask = A.alloc<unsigned short>(nc);
                 lv.qmask = A.alloc<unsigned short>(nc);
                 lv.jcnt = A.alloc<unsigned char>(lv.cont_rows);
+                if (o.collect) {
+                    lv.feat = A.alloc<float>((size_t)lv.cont_rows * 24);
+                    lv.slotw = A.alloc<float>((size_t)lv.cont_rows * 4);
+                }
                 lv.cnt = A.alloc<int>(nc);
             }
         }
@@ -497,6 +509,14 @@ struct Engine : bamg_ctx {
             b0rp = L[0].B.rp;
             b0ci = L[0].B.ci;
             b0v = (double*)L[0].B.v;
+        }
+        if (o.interp == BAMG_INTERP_MLP) {
+            mlp_pk = A.alloc<MlpPack>(1);
+            LAUNCH(k_mlp_pack, 16, BAMG_BLK, s, (const float*)o.mlp_weights, mlp_pk);
+            learn_grid = std::min(1024, nblk(L[0].cont_rows));
+            learn_part = A.alloc<float>(2 * (size_t)learn_grid);
+            learn_acc = A.alloc<double>(2);
+            zero(learn_acc, 2 * sizeof(double));
         }
         // coarsest descriptors: chain c's coarsest level is its last plan entry
         long long woff = 0, boff = 0, aoff = 0;
@@ -517,7 +537,7 @@ struct Engine : bamg_ctx {
             d.am = (o.n_eig > 1) ? std::max(0, std::min({o.arnoldi_m, d.n - 1, HQR_MAXM})) : 0;
             d.brp = L[lc].B.rp; d.bci = L[lc].B.ci; d.bv = L[lc].B.v;
             d.trp = L[lc].Tm.rp; d.tci = L[lc].Tm.ci; d.tv = L[lc].Tm.v;
-            if (gh.ny > GJ_NB) dense_fallback = true;
+            if (gh.ny > GJ_NB || gh.nx > CZ_MAX_NX) dense_fallback = true;
             voff += d.n;
             woff += (long long)d.n * d.n;
             boff += 5LL * d.nx * d.ny * d.ny;
@@ -527,7 +547,8 @@ struct Engine : bamg_ctx {
             nxmax = std::max(nxmax, d.nx);
             cdh.push_back(d);
         }
-        if (dense_fallback && nch > 1) fail(BAMG_EUNSUPPORTED, "batched chains need coarsest grid sides <= %d", GJ_NB);
+        if (dense_fallback && nch > 1)
+            fail(BAMG_EUNSUPPORTED, "batched chains need coarsest grids with ny <= %d and nx <= %d", GJ_NB, CZ_MAX_NX);
         NVt = voff;
         cd = A.upload(cdh);
         Wp = A.alloc<double>(woff);
@@ -748,9 +769,20 @@ struct Engine : bamg_ctx {
         tv_weights(l, use_v);
         std::pair<hipEvent_t, hipEvent_t> ev;
         if (profile) ev = ev_begin();
-        LAUNCH((k_ls_fit<T, T>), nblk(lv.cont_rows), BAMG_BLK, s, lv.cont_rows, (const ChainGeo*)lv.dgeo, lv.ncont, r,
-               use_v, (const int*)nvc, VS, (const T*)lv.U, (const T*)lv.V, (const double*)wts, WS, o.caliber, lv.pc,
-               lv.pv, inject ? c.U : (T*)nullptr, lv.jcnt);
+        if (!use_v && mlp_pk) {
+            // learned form of the first pass: network proposal judged by the fit
+            const int grid = std::min(learn_grid, nblk(lv.cont_rows));
+            LAUNCH((k_ls_fit_learn<T, T, T>), grid, BAMG_BLK, s, lv.cont_rows, (const ChainGeo*)lv.dgeo, lv.ncont, r,
+                   (const T*)lv.U, (const double*)wts, WS, o.caliber, lv.pc, lv.pv, inject ? c.U : (T*)nullptr,
+                   lv.jcnt, (const int*)lv.B.rp, (const int*)lv.B.ci, (const T*)lv.B.v, (const MlpPack*)mlp_pk,
+                   o.mlp_judge, learn_part);
+            LAUNCH(k_learn_tally, 1, BAMG_WAVE, s, grid, (const float*)learn_part, learn_acc);
+        } else {
+            LAUNCH((k_ls_fit<T, T, T>), nblk(lv.cont_rows), BAMG_BLK, s, lv.cont_rows, (const ChainGeo*)lv.dgeo,
+                   lv.ncont, r, use_v, (const int*)nvc, VS, (const T*)lv.U, (const T*)lv.V, (const double*)wts, WS,
+                   o.caliber, lv.pc, lv.pv, inject ? c.U : (T*)nullptr, lv.jcnt, (const int*)lv.B.rp,
+                   (const int*)lv.B.ci, (const T*)lv.B.v, use_v ? (float*)nullptr : lv.feat, lv.slotw);
+        }
         if (profile) ev_end(ev, ev_ls);
         LAUNCH(k_build_q<T>, nblk(c.rows), BAMG_BLK, s, c.rows, (const ChainGeo*)c.dgeo, (const ChainGeo*)lv.dgeo, c.nch,
                lv.pc, lv.qc, lv.qv, lv.qmask);
@@ -1020,7 +1052,7 @@ struct Engine : bamg_ctx {
         coarsest_eigs();
         if (o.stop_after == 2) { finish_setup(t0); return; }
         upleg();
-        if (o.stop_after == 3) { finish_setup(t0); return; }
+        if (o.stop_after == 3 || o.setup_passes == 1) { finish_setup(t0); return; }
         // recompute every P, B, T from U u V
         for (int l = 0; l + 1 < depth; ++l) build_level(l, 1, false, prof && l == 0);
         coarsest_inverse();
@@ -1047,6 +1079,11 @@ struct Engine : bamg_ctx {
         };
         acc(ev_sweep, st.sweep_ms, st.sweep_launches);
         st.tune_ms = sweep_tuner().tune_ms;
+        if (learn_acc) {
+            std::vector<double> la = getn(learn_acc, 2);
+            st.mlp_points = (int64_t)la[0];
+            st.mlp_fallback = (int64_t)la[1];
+        }
         acc(ev_gal, st.galerkin_ms, st.galerkin_launches);
         acc(ev_ls, st.lsfit_ms, st.lsfit_launches);
         // algorithmic bytes of one level-0 launch
@@ -1310,13 +1347,13 @@ struct Engine : bamg_ctx {
                        (const double*)nullptr, (const double*)(sc + 4), SCS, 1, Vk + (size_t)(j + 1) * N);
                 LAUNCH(k_seg_givens, ceil_div(nch, 64), 64, s, nch, j, ld, (const int*)act, Hg, HSg,
                        (const double*)(sc + 4), SCS, cs, sn, g, GS, est);
+                // |g_{j+1}| = 0 also covers a breakdown (||w|| = 0 gives s_j = 0)
                 std::vector<double> e = getn(est, nch);
-                std::vector<double> hn = getn(sc, (size_t)nch * SCS);
                 bool any = false;
                 for (int c = 0; c < nch; ++c) {
                     if (!hact[c]) continue;
                     hkd[c] = j + 1;
-                    if (e[c] <= itol[c] || hn[(size_t)c * SCS + 4] == 0.0) hact[c] = 0;
+                    if (e[c] <= itol[c] || e[c] == 0.0) hact[c] = 0;
                     any |= (bool)hact[c];
                 }
                 HIPCHK(hipMemcpyAsync(act, hact.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
@@ -1431,6 +1468,14 @@ struct Engine : bamg_ctx {
                 copy_out_T(sweep_tmp, (size_t)n * r, 1, 1, dst, bytes);
                 break;
             }
+            case BAMG_X_FEATURES:
+                if (!lv.feat) fail(BAMG_EINVAL, "features are kept only with options.collect on non-coarsest levels");
+                copy_out(lv.feat, (size_t)rows * 24, dst, bytes);
+                break;
+            case BAMG_X_SLOTW:
+                if (!lv.slotw) fail(BAMG_EINVAL, "slot weights are kept only with options.collect on non-coarsest levels");
+                copy_out(lv.slotw, (size_t)rows * 4, dst, bytes);
+                break;
             default: fail(BAMG_EINVAL, "unknown export item %d", what);
         }
     }
@@ -1458,7 +1503,11 @@ void check_options(const bamg_options& o) {
         o.n_eig > 8 || o.gmres_m < 1 || o.gmres_m > 200 || o.arnoldi_m < 1 || o.levels < 0 || o.coarse_max < 1)
         fail(BAMG_EINVAL, "invalid options");
     if (o.cycle_mode < 0 || o.cycle_mode > 2) fail(BAMG_EINVAL, "cycle_mode %d not in {0, 1, 2}", o.cycle_mode);
-    if (o.interp != BAMG_INTERP_LS) fail(BAMG_EUNSUPPORTED, "interpolation mode %d not available", o.interp);
+    if (o.interp != BAMG_INTERP_LS && o.interp != BAMG_INTERP_MLP)
+        fail(BAMG_EINVAL, "unknown interpolation mode %d", o.interp);
+    if (o.interp == BAMG_INTERP_MLP && !o.mlp_weights) fail(BAMG_EINVAL, "learned form needs options.mlp_weights");
+    if (o.setup_passes < 0 || o.setup_passes > 2) fail(BAMG_EINVAL, "setup_passes must be 1 or 2");
+    if (!(o.mlp_judge > 0)) fail(BAMG_EINVAL, "mlp_judge must be positive");
     if (o.precision != BAMG_FP64 && o.precision != BAMG_MIXED) fail(BAMG_EINVAL, "unknown precision %d", o.precision);
 }
 
@@ -1534,6 +1583,8 @@ void bamg_options_default(bamg_options* opt) {
     opt->precision = BAMG_FP64;
     opt->interp = BAMG_INTERP_LS;
     opt->seed = 0;
+    opt->setup_passes = 2;
+    opt->mlp_judge = 2.0f;
 }
 
 const char* bamg_last_error(void) { return g_last_error.c_str(); }
@@ -1613,6 +1664,173 @@ int bamg_apply_vcycle(bamg_handle h, const double* f, double* e) {
     return run_guarded([&] {
         if (!h || !f || !e) fail(BAMG_EINVAL, "NULL argument");
         h->vcycle_apply(f, e);
+    });
+}
+
+// ---- learned interpolation: network calls ------------------------------
+int bamg_mlp_init(uint64_t seed, float* params, void* stream) {
+    return run_guarded([&] {
+        if (!params) fail(BAMG_EINVAL, "NULL params");
+        hipStream_t s = (hipStream_t)stream;
+        LAUNCH(k_mlp_init, ceil_div(MLP_NPARAM, BAMG_BLK), BAMG_BLK, s, seed, params);
+        HIPCHK(hipStreamSynchronize(s));
+    });
+}
+
+namespace {
+// Device copies the network calls share: inputs as padded bfloat16 rows and
+// the packed weights.
+struct MlpBatch {
+    Arena A;
+    unsigned short* xb = nullptr;
+    MlpPack* pk = nullptr;
+    MlpBatch(hipStream_t s) { A.s = s; }
+    ~MlpBatch() { A.release(); }
+    unsigned short* prep(const float* feat, long long n) {
+        unsigned short* x = A.alloc<unsigned short>((size_t)n * MLP_INP);
+        const long long tot = n * MLP_INP;
+        LAUNCH(k_mlp_prep, (int)((tot + BAMG_BLK - 1) / BAMG_BLK), BAMG_BLK, A.s, n, feat, x);
+        return x;
+    }
+    void pack(const float* params) {
+        if (!pk) pk = A.alloc<MlpPack>(1);
+        LAUNCH(k_mlp_pack, 16, BAMG_BLK, A.s, params, pk);
+    }
+};
+
+// Loss (masked MSE normalised by the chunk's own count) and gradient of the
+// points [first, first + bsz) of xb, or of bsz points drawn with `seed` at
+// `step`; grad may be null.  Returns {loss, count} on the host when sync.
+struct MlpStep {
+    Arena& A;
+    int cap;                         // largest batch
+    float *cpart, *cnt, *wpart, *lpart, *lossd, *gbuf;
+    MlpStep(Arena& a, int capacity) : A(a), cap(capacity) {
+        const int nb = ceil_div(cap, BAMG_BLK);
+        cpart = A.alloc<float>(nb);
+        cnt = A.alloc<float>(1);
+        wpart = A.alloc<float>((size_t)nb * 4 * MLP_NPARAM);
+        lpart = A.alloc<float>((size_t)nb * 4);
+        lossd = A.alloc<float>(1);
+        gbuf = A.alloc<float>(MLP_NPARAM);
+    }
+    void run(long long n, int bsz, long long first, uint64_t seed, long long step, const unsigned short* xb,
+             const float* tgt, const MlpPack* pk, float* grad) {
+        const int nb = ceil_div(bsz, BAMG_BLK);
+        LAUNCH(k_mlp_count, nb, BAMG_BLK, A.s, n, bsz, first, seed, step, xb, cpart);
+        LAUNCH(k_mlp_sum, 1, BAMG_BLK, A.s, nb, (const float*)cpart, cnt);
+        LAUNCH(k_mlp_fwdbwd, nb, BAMG_BLK, A.s, n, bsz, first, seed, step, xb, tgt, pk, (const float*)cnt, wpart,
+               lpart);
+        LAUNCH(k_mlp_reduce, ceil_div(MLP_NPARAM, BAMG_BLK), BAMG_BLK, A.s, nb * 4, (const float*)wpart,
+               grad ? grad : gbuf);
+        LAUNCH(k_mlp_sum, 1, BAMG_BLK, A.s, nb * 4, (const float*)lpart, lossd);
+    }
+    std::pair<double, double> read() {
+        float h[2];
+        HIPCHK(hipMemcpyAsync(&h[0], lossd, sizeof(float), hipMemcpyDeviceToHost, A.s));
+        HIPCHK(hipMemcpyAsync(&h[1], cnt, sizeof(float), hipMemcpyDeviceToHost, A.s));
+        HIPCHK(hipStreamSynchronize(A.s));
+        return {h[0], h[1]};
+    }
+};
+
+// Loss over a whole set, in chunks, normalised by the set's total count.
+double mlp_set_loss(MlpStep& st, const unsigned short* xb, const float* tgt, long long n, const MlpPack* pk) {
+    double num = 0, den = 0;
+    for (long long f = 0; f < n; f += st.cap) {
+        const int b = (int)std::min<long long>(st.cap, n - f);
+        st.run(n, b, f, 0, 0, xb, tgt, pk, nullptr);
+        auto lc = st.read();
+        num += lc.first * std::max(1.0, lc.second);
+        den += lc.second;
+    }
+    return den > 0 ? num / den : 0.0;
+}
+}  // namespace
+
+int bamg_mlp_forward(const float* feat, int64_t n, const float* params, float* out, void* stream) {
+    return run_guarded([&] {
+        if (!feat || !params || !out) fail(BAMG_EINVAL, "NULL argument");
+        if (n < 0 || n > (1LL << 30)) fail(BAMG_EINVAL, "n out of range");
+        if (n == 0) return;
+        hipStream_t s = (hipStream_t)stream;
+        MlpBatch mb(s);
+        unsigned short* xb = mb.prep(feat, n);
+        mb.pack(params);
+        const int grid = (int)std::min<long long>(1024, (n + 255) / 256);
+        LAUNCH(k_mlp_infer, grid, BAMG_BLK, s, (long long)n, (const unsigned short*)xb, (const MlpPack*)mb.pk, out);
+        HIPCHK(hipStreamSynchronize(s));
+    });
+}
+
+int bamg_mlp_loss_grad(const float* feat, const float* tgt, int64_t n, const float* params, float* grad,
+                       double* loss, void* stream) {
+    return run_guarded([&] {
+        if (!feat || !tgt || !params || !grad) fail(BAMG_EINVAL, "NULL argument");
+        if (n < 1 || n > (1 << 24)) fail(BAMG_EINVAL, "n out of range [1, 2^24]");
+        hipStream_t s = (hipStream_t)stream;
+        MlpBatch mb(s);
+        unsigned short* xb = mb.prep(feat, n);
+        mb.pack(params);
+        MlpStep st(mb.A, (int)n);
+        st.run(n, (int)n, 0, 0, 0, xb, tgt, mb.pk, grad);
+        auto lc = st.read();
+        if (loss) *loss = lc.first;
+    });
+}
+
+int bamg_mlp_train(const float* feat, const float* tgt, int64_t n, const float* vfeat, const float* vtgt, int64_t nv,
+                   float* params, const bamg_mlp_train_opts* opt, bamg_mlp_train_info* info, void* stream) {
+    return run_guarded([&] {
+        auto t0 = std::chrono::steady_clock::now();
+        if (!feat || !tgt || !params) fail(BAMG_EINVAL, "NULL argument");
+        if (n < 1 || n > (1LL << 30) || nv < 0 || (nv > 0 && (!vfeat || !vtgt))) fail(BAMG_EINVAL, "bad sizes");
+        bamg_mlp_train_opts o{8, 4096, 1e-3f, 0.9f, 0.999f, 1e-8f, 6};
+        if (opt) o = *opt;
+        if (o.epochs < 0 || o.batch < 256 || o.batch % 256 || o.batch > (1 << 20) || !(o.lr > 0))
+            fail(BAMG_EINVAL, "bad training options");
+        hipStream_t s = (hipStream_t)stream;
+        MlpBatch mb(s);
+        unsigned short* xb = mb.prep(feat, n);
+        unsigned short* vxb = nv > 0 ? mb.prep(vfeat, nv) : nullptr;
+        float* m = mb.A.alloc<float>(MLP_NPARAM);
+        float* v = mb.A.alloc<float>(MLP_NPARAM);
+        HIPCHK(hipMemsetAsync(m, 0, MLP_NPARAM * sizeof(float), s));
+        HIPCHK(hipMemsetAsync(v, 0, MLP_NPARAM * sizeof(float), s));
+        MlpStep st(mb.A, std::max(o.batch, 65536));
+        bamg_mlp_train_info inf{};
+        mb.pack(params);
+        if (nv > 0) inf.val_loss_first = mlp_set_loss(st, vxb, vtgt, nv, mb.pk);
+        const long long spe = (n + o.batch - 1) / o.batch;
+        long long step = 0;
+        for (int ep = 0; ep < o.epochs; ++ep) {
+            for (long long k = 0; k < spe; ++k, ++step) {
+                const long long first = o.seed ? 0 : k * o.batch;
+                const int bsz = o.seed ? (int)std::min<long long>(o.batch, n)
+                                       : (int)std::min<long long>(o.batch, n - first);
+                mb.pack(params);
+                st.run(n, bsz, first, o.seed, step, xb, tgt, mb.pk, st.gbuf);
+                const double t = (double)(step + 1);
+                const float c1 = (float)(1.0 / (1.0 - std::pow((double)o.beta1, t)));
+                const float c2 = (float)(1.0 / (1.0 - std::pow((double)o.beta2, t)));
+                LAUNCH(k_mlp_adam, ceil_div(MLP_NPARAM, BAMG_BLK), BAMG_BLK, s, params, m, v, (const float*)st.gbuf,
+                       o.lr, o.beta1, o.beta2, o.eps, c1, c2);
+                if (step == 0) inf.train_loss_first = st.read().first;
+            }
+            if (spe > 0) inf.train_loss_last = st.read().first;
+            if (nv > 0 && inf.val_len < 64) {
+                mb.pack(params);
+                inf.val_history[inf.val_len++] = mlp_set_loss(st, vxb, vtgt, nv, mb.pk);
+            }
+        }
+        inf.steps = (int)step;
+        if (nv > 0) {
+            mb.pack(params);
+            inf.val_loss_last = mlp_set_loss(st, vxb, vtgt, nv, mb.pk);
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        inf.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (info) *info = inf;
     });
 }
 

@@ -15,6 +15,10 @@
 #include "common.h"
 #include "k_dense.h"
 
+// Block-LU path limits: block side ny <= GJ_NB, block rows nx <= CZ_MAX_NX
+// (larger coarsest grids take the dense Gauss-Jordan path).
+#define CZ_MAX_NX 256
+
 struct CoarseDesc {
     int n, nx, ny, periodic;
     int row0;                 // first row of the chain on its coarsest level
@@ -307,20 +311,65 @@ __device__ __forceinline__ void cz_put(const double X[4][4], double (*Xs)[GJ_NB 
         for (int q = 0; q < 4; ++q) Xs[tr + a][tc + q] = X[a][q];
 }
 
+// The blocks a substitution workgroup multiplies by, in the order it uses
+// them (index part * nx + k into the chain's block storage).
+__device__ int cz_subst_sequence(int K, bool arrow, int* seq) {
+    int m = 0;
+    for (int s = 0; s < K; ++s) {
+        if (s >= 1) seq[m++] = 2 * (K + 1) + s;               // Lo_s
+        if (arrow && s < K - 1) seq[m++] = 4 * (K + 1) + s;   // Rw_s
+        if (s == K - 1) seq[m++] = 2 * (K + 1) + K;           // Lo_K
+    }
+    seq[m++] = K;                                              // Dinv_K
+    for (int k = K - 1; k >= 0; --k) {
+        seq[m++] = (K + 1) + k;                                // Up_k
+        if (arrow && k < K - 1) seq[m++] = 3 * (K + 1) + k;   // Cl_k
+        seq[m++] = k;                                          // Dinv_k
+    }
+    return m;
+}
+
 __global__ void __launch_bounds__(BAMG_BLK)
 k_cz_subst(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const double* __restrict__ Fp) {
     __shared__ double Ms[GJ_NB][GJ_NB + 1];
     __shared__ double Xs[GJ_NB][GJ_NB + 1];
     __shared__ double Ks[GJ_NB][GJ_NB + 1];
+    __shared__ int seq[5 * CZ_MAX_NX + 8];
+    __shared__ int nseq;
     const CoarseDesc d = cd[blockIdx.y];
     const int K = d.nx - 1, b = d.ny, n = d.n;
     const int c0 = blockIdx.x * 64;
     if (n < 2 || c0 >= n) return;
     const bool arrow = d.periodic && d.nx >= 3;
-    double* F = (double*)Fp;
+    const double* F = Fp + d.boff;
     double* W = Wp + d.woff;
     const int w = min(64, n - c0);
     const int tid = threadIdx.x, tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+    const long long bb = (long long)b * b;
+    if (tid == 0) nseq = cz_subst_sequence(K, arrow, seq);
+    __syncthreads();
+    // The next block of the sequence is loaded into registers while the
+    // current one is in use; next_block() moves it to Ms (the caller has
+    // synchronised) and starts loading the one after.
+    double pre[GJ_NB * GJ_NB / BAMG_BLK];
+    int sidx = 0;
+    auto fetch = [&](int i) {
+        const double* M = F + (long long)seq[i] * bb;
+#pragma unroll
+        for (int q = 0; q < GJ_NB * GJ_NB / BAMG_BLK; ++q) {
+            const int e = tid + q * BAMG_BLK, r = e / GJ_NB, c = e % GJ_NB;
+            pre[q] = (r < b && c < b) ? M[r * b + c] : 0.0;
+        }
+    };
+    auto next_block = [&]() {
+#pragma unroll
+        for (int q = 0; q < GJ_NB * GJ_NB / BAMG_BLK; ++q) {
+            const int e = tid + q * BAMG_BLK;
+            Ms[e / GJ_NB][e % GJ_NB] = pre[q];
+        }
+        if (++sidx < nseq) fetch(sidx);
+    };
+    fetch(0);
     auto store = [&](int blk, const double X[4][4]) {
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -337,7 +386,7 @@ k_cz_subst(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const dou
         cz_ident(s, b, c0, w, tr, tc, T);
         if (s >= 1) {                                // Xs holds Y_{s-1}
             __syncthreads();
-            cz_load_blk(b, cz_blk(F, d, 2, s), Ms);
+            next_block();                            // Lo_s
             __syncthreads();
             cz_mac(b, Ms, Xs, tr, tc, T, -1.0);
         }
@@ -345,20 +394,20 @@ k_cz_subst(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const dou
         cz_put(T, Xs, tr, tc);
         store(s, T);
         if (arrow && s < K - 1) {
-            cz_load_blk(b, cz_blk(F, d, 4, s), Ms);
+            next_block();                            // Rw_s
             __syncthreads();
             cz_mac(b, Ms, Xs, tr, tc, TK, -1.0);
         }
         if (s == K - 1) {
             __syncthreads();
-            cz_load_blk(b, cz_blk(F, d, 2, K), Ms);
+            next_block();                            // Lo_K
             __syncthreads();
             cz_mac(b, Ms, Xs, tr, tc, TK, -1.0);
         }
     }
     // X_K = Dinv_K Y_K, kept in Ks for the arrow terms
     __syncthreads();
-    cz_load_blk(b, cz_blk(F, d, 0, K), Ms);
+    next_block();                                    // Dinv_K
     cz_put(TK, Xs, tr, tc);
     __syncthreads();
 #pragma unroll
@@ -381,17 +430,17 @@ k_cz_subst(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const dou
                 U[a][q] = (r < b && c < w) ? W[(size_t)(k * b + r) * n + c0 + c] : 0.0;
             }
         __syncthreads();
-        cz_load_blk(b, cz_blk(F, d, 1, k), Ms);
+        next_block();                                // Up_k
         __syncthreads();
         cz_mac(b, Ms, Xs, tr, tc, U, -1.0);
         if (arrow && k < K - 1) {
             __syncthreads();
-            cz_load_blk(b, cz_blk(F, d, 3, k), Ms);
+            next_block();                            // Cl_k
             __syncthreads();
             cz_mac(b, Ms, Ks, tr, tc, U, -1.0);
         }
         __syncthreads();
-        cz_load_blk(b, cz_blk(F, d, 0, k), Ms);
+        next_block();                                // Dinv_k
         cz_put(U, Xs, tr, tc);
         __syncthreads();
 #pragma unroll

@@ -537,37 +537,22 @@ __device__ __forceinline__ bool chol4(const double G[4][4], const double b[4], i
 // (strict minimum, ties to the lower slot) until |J| >= caliber; a candidate
 // g is admissible when det(G_{J+g}) / det(G_J) > 1e-10 G_gg (its Schur
 // complement pivot).  Gram and solves in FP64 whatever the storage type.
-// jcnt (optional): |J_i| per fine point, for the restriction of the cycle.
-template <typename T, typename MP>
-__global__ void __launch_bounds__(BAMG_BLK)
-k_ls_fit(int n, const ChainGeo* __restrict__ geo, int nch, int Ru, int use_v, const int* __restrict__ nvc,
-         int VS, const T* __restrict__ U, const T* __restrict__ V, const double* __restrict__ wall, int WS,
-         int caliber, int* __restrict__ pc, MP* __restrict__ pv, T* __restrict__ inject,
-         unsigned char* __restrict__ jcnt) {
-    int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
-    if (i >= n) return;
-    const int ch = find_chain(geo, nch, i);
-    const ChainGeo g = geo[ch];
-    const int Rv = use_v ? nvc[ch] : 0;
-    const double* __restrict__ w = wall + (size_t)ch * WS;
+struct LsPoint {
+    double G[4][4], b[4], sigma;
+    double p[4];          // fitted weights in slot order (zero outside J)
+    double Lls;           // the functional at the fit
+    int sf[4], sc[4];     // fine / coarse index of each slot
+    int valid, J;         // slot masks: non-empty, selected
+};
+
+template <typename T>
+__device__ __forceinline__ void ls_point(int i, const ChainGeo& g, int ia, int ib, int Ru, int Rv, int VS,
+                                         const T* __restrict__ U, const T* __restrict__ V,
+                                         const double* __restrict__ w, int caliber, LsPoint& P) {
     const int ncy = g.ncy;
-    const int li = i - g.off;
-    const int ia = (int)g.dy.div((uint32_t)li), ib = li - ia * g.ny;
-    if (((ia | ib) & 1) == 0) {
-        int I = g.coff + (ia >> 1) * ncy + (ib >> 1);
-        pc[(size_t)i * 4] = I; pv[(size_t)i * 4] = (MP)1;
-#pragma unroll
-        for (int s = 1; s < 4; ++s) { pc[(size_t)i * 4 + s] = -1; pv[(size_t)i * 4 + s] = (MP)0; }
-        if (inject)
-            for (int k = 0; k < Ru; ++k) inject[(size_t)I * Ru + k] = U[(size_t)i * Ru + k];
-        if (jcnt) jcnt[i] = 1;
-        return;
-    }
-    // neighbourhood slots
-    int sf[4], sc[4];
     int ns = 0;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) { sf[s] = i; sc[s] = -1; }
+    for (int s = 0; s < 4; ++s) { P.sf[s] = i; P.sc[s] = -1; }
 #pragma unroll
     for (int da = -1; da <= 1; ++da)
 #pragma unroll
@@ -584,17 +569,18 @@ k_ls_fit(int n, const ChainGeo* __restrict__ geo, int nch, int Ru, int use_v, co
             // at most 4 coarse points in the box; ns < 4 always holds here
 #pragma unroll
             for (int s = 0; s < 4; ++s)
-                if (s == ns) { sf[s] = g.off + na * g.ny + nb; sc[s] = g.coff + (na >> 1) * ncy + (nb >> 1); }
+                if (s == ns) { P.sf[s] = g.off + na * g.ny + nb; P.sc[s] = g.coff + (na >> 1) * ncy + (nb >> 1); }
             ++ns;
         }
-    int valid = (1 << ns) - 1;
+    const int valid = (1 << ns) - 1;
+    P.valid = valid;
     // weighted Gram, right-hand side and sigma over all test vectors
-    double G[4][4], b[4], sigma = 0;
+    double sigma = 0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        b[s] = 0;
+        P.b[s] = 0;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) G[s][t] = 0;
+        for (int t = 0; t < 4; ++t) P.G[s][t] = 0;
     }
     // U columns, then V columns (test vectors in a fixed order k = 0..R-1)
     for (int part = 0; part < 2; ++part) {
@@ -608,21 +594,22 @@ k_ls_fit(int n, const ChainGeo* __restrict__ geo, int nch, int Ru, int use_v, co
             double xi = (double)Xp[(size_t)i * ld + kk];
             double xs[4];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) xs[s] = ((valid >> s) & 1) ? (double)Xp[(size_t)sf[s] * ld + kk] : 0.0;
+            for (int s = 0; s < 4; ++s) xs[s] = ((valid >> s) & 1) ? (double)Xp[(size_t)P.sf[s] * ld + kk] : 0.0;
             sigma += wk * xi * xi;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 double ws = wk * xs[s];
-                b[s] += ws * xi;
+                P.b[s] += ws * xi;
 #pragma unroll
-                for (int t = 0; t <= s; ++t) G[s][t] += ws * xs[t];
+                for (int t = 0; t <= s; ++t) P.G[s][t] += ws * xs[t];
             }
         }
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int t = s + 1; t < 4; ++t) G[s][t] = G[t][s];
+        for (int t = s + 1; t < 4; ++t) P.G[s][t] = P.G[t][s];
+    P.sigma = sigma;
     // greedy selection (Algorithm 2)
     int J = 0, nsel = 0;
     double L[4][4], z[4], detJ = 1.0;
@@ -636,8 +623,8 @@ k_ls_fit(int n, const ChainGeo* __restrict__ geo, int nch, int Ru, int use_v, co
             if (!((valid >> c) & 1) || ((J >> c) & 1)) continue;
             int S = J | (1 << c);
             double det;
-            bool ok = chol4(G, b, S, L, z, det);
-            if (!ok || !(det > 1e-10 * G[c][c] * detJ)) continue;
+            bool ok = chol4(P.G, P.b, S, L, z, det);
+            if (!ok || !(det > 1e-10 * P.G[c][c] * detJ)) continue;
             double Lv = sigma;
 #pragma unroll
             for (int s = 0; s < 4; ++s) Lv -= z[s] * z[s];
@@ -647,27 +634,40 @@ k_ls_fit(int n, const ChainGeo* __restrict__ geo, int nch, int Ru, int use_v, co
         J |= 1 << best;
         ++nsel;
         double det;
-        chol4(G, b, J, L, z, det);
+        chol4(P.G, P.b, J, L, z, det);
         detJ = det;
     }
-    double p[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) P.p[s] = 0.0;
     if (J == 0) {
         J = 1;
-        p[0] = 1.0;
+        P.p[0] = 1.0;
+        P.Lls = sigma - 2.0 * P.b[0] + P.G[0][0];
     } else {
         double det;
-        chol4(G, b, J, L, z, det);
+        chol4(P.G, P.b, J, L, z, det);
+        double Lv = sigma;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) Lv -= z[s] * z[s];
+        P.Lls = Lv;
         // back substitution L^T p = z on J
 #pragma unroll
         for (int j = 3; j >= 0; --j) {
             if (!((J >> j) & 1)) continue;
             double s = z[j];
 #pragma unroll
-            for (int k = j + 1; k < 4; ++k) s -= L[k][j] * p[k];
-            p[j] = s / L[j][j];
+            for (int k = j + 1; k < 4; ++k) s -= L[k][j] * P.p[k];
+            P.p[j] = s / L[j][j];
         }
     }
-    // write the used slots in ascending coarse column (rank of each slot)
+    P.J = J;
+}
+
+// Row i of P from weights p on the slots in mask J, in ascending coarse column;
+// returns the number of entries.
+template <typename MP>
+__device__ __forceinline__ int write_prow(int i, int J, const int sc[4], const double p[4], int* __restrict__ pc,
+                                          MP* __restrict__ pv) {
     int cnt = 0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) cnt += (J >> s) & 1;
@@ -682,7 +682,92 @@ k_ls_fit(int n, const ChainGeo* __restrict__ geo, int nch, int Ru, int use_v, co
         pv[(size_t)i * 4 + rank] = (MP)p[s];
     }
     for (int s = cnt; s < 4; ++s) { pc[(size_t)i * 4 + s] = -1; pv[(size_t)i * 4 + s] = (MP)0; }
+    return cnt;
+}
+
+// The 24 scale-free features of an F point (learned form):
+//   [valid slot mask (4) | -b_ij / b_ii at the 8 neighbour offsets in
+//    lexicographic (da, db) order (8) | b_s / G_ss (4) |
+//    b_s / sqrt(sigma G_ss) (4) | sqrt(G_ss / sigma) (4)], zero for empty slots.
+template <typename M>
+__device__ __forceinline__ void point_features(const LsPoint& P, int i, const ChainGeo& g, int ia, int ib,
+                                               const int* __restrict__ rp, const int* __restrict__ ci,
+                                               const M* __restrict__ bv, float f[24]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) f[s] = ((P.valid >> s) & 1) ? 1.0f : 0.0f;
+    double st[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) st[k] = 0.0;
+    double diag = 1.0;
+    const int p0 = rp[i], p1 = rp[i + 1];
+    for (int p = p0; p < p1; ++p)
+        if (ci[p] == i) diag = (double)bv[p];
+    for (int p = p0; p < p1; ++p) {
+        const int j = ci[p];
+        if (j == i) continue;
+        const int lj = j - g.off;
+        const int ja = (int)g.dy.div((uint32_t)lj), jb = lj - ja * g.ny;
+        const int da = grid_delta(ia, ja, g.nx, g.periodic), db = grid_delta(ib, jb, g.ny, g.periodic);
+        int k = (da + 1) * 3 + (db + 1);
+        k = k > 4 ? k - 1 : k;
+        const double val = -(double)bv[p] / diag;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) st[t] += (t == k) ? val : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) f[4 + k] = (float)st[k];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const double Gss = P.G[s][s];
+        const bool ok = ((P.valid >> s) & 1) && Gss > 0.0 && P.sigma > 0.0;
+        f[12 + s] = ok ? (float)(P.b[s] / Gss) : 0.0f;
+        f[16 + s] = ok ? (float)(P.b[s] / sqrt(P.sigma * Gss)) : 0.0f;
+        f[20 + s] = ok ? (float)sqrt(Gss / P.sigma) : 0.0f;
+    }
+}
+
+// jcnt (optional): |J_i| per fine point, for the restriction of the cycle.
+// feat_out (optional, n x 24 FP32): the features of every F point (zero rows
+// for C points); slotw_out (optional, n x 4 FP32): the fitted weights in slot
+// order.  Both only serve to collect training data for the learned form.
+template <typename T, typename MP, typename M>
+__global__ void __launch_bounds__(BAMG_BLK)
+k_ls_fit(int n, const ChainGeo* __restrict__ geo, int nch, int Ru, int use_v, const int* __restrict__ nvc,
+         int VS, const T* __restrict__ U, const T* __restrict__ V, const double* __restrict__ wall, int WS,
+         int caliber, int* __restrict__ pc, MP* __restrict__ pv, T* __restrict__ inject,
+         unsigned char* __restrict__ jcnt, const int* __restrict__ brp, const int* __restrict__ bci,
+         const M* __restrict__ bv, float* __restrict__ feat_out, float* __restrict__ slotw_out) {
+    int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    const int ch = find_chain(geo, nch, i);
+    const ChainGeo g = geo[ch];
+    const int li = i - g.off;
+    const int ia = (int)g.dy.div((uint32_t)li), ib = li - ia * g.ny;
+    if (((ia | ib) & 1) == 0) {
+        int I = g.coff + (ia >> 1) * g.ncy + (ib >> 1);
+        pc[(size_t)i * 4] = I; pv[(size_t)i * 4] = (MP)1;
+#pragma unroll
+        for (int s = 1; s < 4; ++s) { pc[(size_t)i * 4 + s] = -1; pv[(size_t)i * 4 + s] = (MP)0; }
+        if (inject)
+            for (int k = 0; k < Ru; ++k) inject[(size_t)I * Ru + k] = U[(size_t)i * Ru + k];
+        if (jcnt) jcnt[i] = 1;
+        if (feat_out)
+            for (int k = 0; k < 24; ++k) feat_out[(size_t)i * 24 + k] = 0.0f;
+        if (slotw_out)
+            for (int k = 0; k < 4; ++k) slotw_out[(size_t)i * 4 + k] = 0.0f;
+        return;
+    }
+    LsPoint P;
+    ls_point<T>(i, g, ia, ib, Ru, use_v ? nvc[ch] : 0, VS, U, V, wall + (size_t)ch * WS, caliber, P);
+    const int cnt = write_prow<MP>(i, P.J, P.sc, P.p, pc, pv);
     if (jcnt) jcnt[i] = (unsigned char)cnt;
+    if (feat_out) {
+        float f[24];
+        point_features<M>(P, i, g, ia, ib, brp, bci, bv, f);
+        for (int k = 0; k < 24; ++k) feat_out[(size_t)i * 24 + k] = f[k];
+    }
+    if (slotw_out)
+        for (int k = 0; k < 4; ++k) slotw_out[(size_t)i * 4 + k] = (float)P.p[k];
 }
 
 // ---------------------------------------------------------------- Q
