@@ -143,8 +143,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["tandem", "batch64"], default="tandem",
-                    help="tandem: one tandem queue (default N=2047, n=4.2M); batch64: 64 mixed chains in one handle")
+    ap.add_argument("--workload", choices=["tandem", "batch64", "learned"], default="tandem",
+                    help="tandem: one tandem queue (default N=2047, n=4.2M); batch64: 64 mixed chains in one handle; "
+                         "learned: train the interpolation network on 32 jittered tandems (untimed), then time the "
+                         "learned form on the tandem queue against the plain forms")
+    ap.add_argument("--train-chains", type=int, default=32)
+    ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--N", type=int, default=2047, help="tandem queue capacity (side N+1)")
     ap.add_argument("--levels", type=int, default=6)
     ap.add_argument("--r", type=int, default=12)
@@ -221,6 +225,62 @@ def main():
         }
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline(args)
+    elif args.workload == "learned":
+        from paper_1004_1451_amd import learned as LRN
+        t0 = time.perf_counter()
+        train = C.training_chains(args.train_chains)
+        params, tinfo, sizes = LRN.train(train, r=args.r, levels=args.levels, n_val=4, epochs=args.epochs)
+        train_s = time.perf_counter() - t0
+        ch = C.tandem_queue(args.N)
+        rp, ci, v = B.device_csr(ch)
+        x = torch.empty(ch.n, dtype=torch.float64, device="cuda")
+        forms = {
+            "plain_fp64": dict(precision=B.FP64),
+            "mixed_ls": dict(precision=B.MIXED),
+            "mixed_ls_1pass": dict(precision=B.MIXED, setup_passes=1),
+            "mixed_learned_1pass": dict(precision=B.MIXED, interp=B.INTERP_MLP, mlp_weights=params.data_ptr(),
+                                        setup_passes=1),
+            "mixed_learned": dict(precision=B.MIXED, interp=B.INTERP_MLP, mlp_weights=params.data_ptr()),
+        }
+        res = {}
+        for name, kw in forms.items():
+            opts = B.default_options(levels=args.levels, profile=1, **kw)
+
+            def step():
+                h = B.Hierarchy(ch.n, rp, ci, v, (ch.nx, ch.ny, 0), args.r, opts)
+                info = h.solve(x, args.tol, 300)
+                st = h.stats()
+                h.close()
+                return info, st
+
+            sec_f, rr = _timed(step, args)
+            info, st = rr[-1]
+            res[name] = {"ms_per_step": round(sec_f * 1e3, 3), "cycles": info.cycles,
+                         "residual_l1": info.residual_l1, "converged": bool(info.converged),
+                         "setup_ms": round(st.t_setup_ms, 3), "solve_ms": round(st.t_solve_ms, 3)}
+            if kw.get("interp") == B.INTERP_MLP:
+                res[name]["fallback_fraction"] = round(st.mlp_fallback / max(1, st.mlp_points), 4)
+            if name == "mixed_learned_1pass":
+                sec, stats = sec_f, [b for _, b in rr]
+        sweep_ms, roof = _roofline(stats, traffic if args.precision == "mixed" else None)
+        roof["kernel"] += ", R=%d" % args.r
+        out = {
+            "metric": "setup+solve seconds to ||Bx||_1/||x||_1<=1e-10 at n=4.2M, learned + mixed form",
+            "value": round(sec, 6), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(sec * 1e3, 3), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32+f64+bf16", "data": "synthetic",
+            "config": {"workload": f"tandem queue N={args.N} (n={ch.n:,}), r={args.r}, {args.levels} levels, "
+                                   f"tol {args.tol:g}; network trained on {args.train_chains} jittered tandems "
+                                   f"N in [255,1023]", "precision": "mixed+learned"},
+            "roofline": roof,
+            "detail": {"forms": res, "train_s": round(train_s, 2), "train_points": sizes[0], "val_points": sizes[1],
+                       "train_steps": tinfo.steps, "train_ms": round(tinfo.ms, 1),
+                       "val_loss_first": tinfo.val_loss_first, "val_loss_last": tinfo.val_loss_last,
+                       "learned_vs_plain_fp64": round(res["plain_fp64"]["ms_per_step"] /
+                                                      res["mixed_learned_1pass"]["ms_per_step"], 3),
+                       "learned_vs_mixed_ls_1pass": round(res["mixed_ls_1pass"]["ms_per_step"] /
+                                                          res["mixed_learned_1pass"]["ms_per_step"], 3)},
+        }
     else:
         chains = C.batch_mix(64)
         db = B.DeviceBatch(chains)

@@ -174,6 +174,8 @@ typedef struct {
                                (zero rows for C points); needs options.collect */
 #define BAMG_X_SLOTW 18     /* float[n*4] final interpolation weights in slot
                                order (lexicographic (da, db)); needs collect  */
+#define BAMG_X_SLOTW0 19    /* float[n*4] the first pass's fitted weights in slot
+                               order (least-squares form); needs collect      */
 
 /* Fill *opt with the defaults: levels 0, coarse_max 1024, nu_setup 4,
    V(2,2), omega 0.7, caliber 4, n_eig 6, arnoldi_m 64, gmres_m 50,
@@ -264,7 +266,8 @@ int bamg_apply_vcycle(bamg_handle h, const double* f, double* e);
    A 24-64-64-4 ReLU network maps the 24 features of an F point's
    least-squares problem (Section 3.2, eq. LSfuncrowi: the slot mask, the
    operator row -b_ij/b_ii at the 8 neighbour offsets, b_s/G_ss,
-   b_s/sqrt(sigma G_ss), sqrt(G_ss/sigma)) to its 4 slot weights.  Params:
+   b_s/sqrt(sigma G_ss), sqrt(G_ss/sigma)) to a correction of its 4 fitted
+   slot weights (the setup adds it to the first-pass fit, then judges).  Params:
    BAMG_MLP_NPARAM FP32 values, row-major W1[64][24], b1[64], W2[64][64],
    b2[64], W3[4][64], b3[4].  Every product runs on the matrix cores with
    bfloat16 operands (round to nearest even) and FP32 accumulation.  Features

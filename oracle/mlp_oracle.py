@@ -4,12 +4,13 @@ TEST INFRASTRUCTURE ONLY: imported by tests/, __graft_entry__.smoke() and
 bench.py's cpu_baseline leg, never by the product path.
 
 The paper's method fits each interpolation row by least squares (Section 3.2,
-Algorithm 2).  The learned form replaces the first-pass fit by a small network
-that predicts, from features of the same local least-squares problem, the
-weights the method settles on after its recomputation pass; the fit stays as
-judge and fallback.  None of this is in the paper: the features, network and
-training follow the project's own specification (24 features, 24-64-64-4
-ReLU network, masked mean-squared loss, Adam).
+Algorithm 2).  The learned form corrects the first-pass fit with a small
+network that predicts, from features of the same local least-squares problem,
+how far the weights the method settles on after its recomputation pass are
+from the first-pass fit; the fit stays as judge and fallback.  None of this is
+in the paper: the features, network and training follow the project's own
+specification (24 features, 24-64-64-4 ReLU network, masked mean-squared
+loss, Adam).
 
 Everything here is written out plainly:
   * features(): 24 scale-free numbers per fine point from the weighted Gram

@@ -23,7 +23,7 @@ USE_GUESS = 1
 
 X_B_ROWPTR, X_B_COL, X_B_VAL, X_T_ROWPTR, X_T_COL, X_T_VAL = 1, 2, 3, 4, 5, 6
 X_P_COL, X_P_VAL, X_U, X_V, X_LAMBDA, X_VKIND, X_X0, X_W, X_Y, X_U0 = 7, 8, 9, 10, 11, 12, 13, 14, 15, 16
-X_FEATURES, X_SLOTW = 17, 18
+X_FEATURES, X_SLOTW, X_SLOTW0 = 17, 18, 19
 MLP_NPARAM = 6020
 
 ERROR_NAMES = {EINVAL: "EINVAL", ENOTSTOCH: "ENOTSTOCH", EZERODIAG: "EZERODIAG", EUNSUPPORTED: "EUNSUPPORTED",
@@ -214,7 +214,8 @@ class Hierarchy:
                  X_P_COL: (4 * n, np.int32), X_P_VAL: (4 * n, np.float64), X_U: (n * li.r, np.float64),
                  X_V: (n * li.n_v, np.float64), X_LAMBDA: (2 * li.n_v, np.float64), X_VKIND: (li.n_v, np.int32),
                  X_X0: (n, np.float64), X_W: (n * n, np.float64), X_Y: (n, np.float64),
-                 X_U0: (n * li.r, np.float64), X_FEATURES: (n * 24, np.float32), X_SLOTW: (n * 4, np.float32)}
+                 X_U0: (n * li.r, np.float64), X_FEATURES: (n * 24, np.float32), X_SLOTW: (n * 4, np.float32),
+                 X_SLOTW0: (n * 4, np.float32)}
         cnt, dt = sizes[what]
         out = np.empty(int(cnt), dtype=dt)
         _check(load().bamg_export(self._h, int(l), int(what), out.ctypes.data_as(C.c_void_p), out.nbytes))

@@ -30,6 +30,7 @@ STREAM_JITTER = 3
 STREAM_BATCH = 4
 STREAM_MLP_INIT = 5
 STREAM_MLP_SHUFFLE = 6
+STREAM_TRAIN_SIZES = 8   # (stream 7 is the coarsest Arnoldi start vector)
 
 
 def splitmix64(key: np.ndarray) -> np.ndarray:
@@ -189,6 +190,15 @@ def batch_mix(n_chains: int = 64, seed: int = 0):
             side = max(32, side - side % 16)
             chains.append(weighted_lattice(side, seed=seed, chain_id=c))
     return chains
+
+
+def training_chains(n_chains: int = 32, seed: int = 0, n_min: int = 255, n_max: int = 1023):
+    """Training set of the learned form: jittered tandem queues (rates times
+    1 +- 0.2) with N = n_min + floor((n_max - n_min + 1) u), u drawn from
+    (seed, STREAM_TRAIN_SIZES, chain)."""
+    u = uniform(seed, STREAM_TRAIN_SIZES, np.arange(n_chains))
+    return [tandem_queue(n_min + int(u[c] * (n_max - n_min + 1)), jitter=0.2, seed=seed, chain_id=1000 + c)
+            for c in range(n_chains)]
 
 
 def config_chain(cfg: int, seed: int = 0) -> Chain:

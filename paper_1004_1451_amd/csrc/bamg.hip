@@ -266,6 +266,7 @@ struct Level {
     unsigned char* jcnt = nullptr;   // |J_i| per continuing row
     float* feat = nullptr;           // collected first-pass features (rows x 24)
     float* slotw = nullptr;          // collected final slot weights (rows x 4)
+    float* slotw0 = nullptr;         // collected first-pass slot weights (rows x 4)
     int* cnt = nullptr;
     bool zero_into_e2 = false;       // first smoothing sweep target (fixed buffers)
 };
@@ -497,6 +498,7 @@ struct Engine : bamg_ctx {
                 if (o.collect) {
                     lv.feat = A.alloc<float>((size_t)lv.cont_rows * 24);
                     lv.slotw = A.alloc<float>((size_t)lv.cont_rows * 4);
+                    lv.slotw0 = A.alloc<float>((size_t)lv.cont_rows * 4);
                 }
                 lv.cnt = A.alloc<int>(nc);
             }
@@ -781,7 +783,8 @@ struct Engine : bamg_ctx {
             LAUNCH((k_ls_fit<T, T, T>), nblk(lv.cont_rows), BAMG_BLK, s, lv.cont_rows, (const ChainGeo*)lv.dgeo,
                    lv.ncont, r, use_v, (const int*)nvc, VS, (const T*)lv.U, (const T*)lv.V, (const double*)wts, WS,
                    o.caliber, lv.pc, lv.pv, inject ? c.U : (T*)nullptr, lv.jcnt, (const int*)lv.B.rp,
-                   (const int*)lv.B.ci, (const T*)lv.B.v, use_v ? (float*)nullptr : lv.feat, lv.slotw);
+                   (const int*)lv.B.ci, (const T*)lv.B.v, use_v ? (float*)nullptr : lv.feat,
+                   use_v ? lv.slotw : lv.slotw0);
         }
         if (profile) ev_end(ev, ev_ls);
         LAUNCH(k_build_q<T>, nblk(c.rows), BAMG_BLK, s, c.rows, (const ChainGeo*)c.dgeo, (const ChainGeo*)lv.dgeo, c.nch,
@@ -1473,8 +1476,11 @@ struct Engine : bamg_ctx {
                 copy_out(lv.feat, (size_t)rows * 24, dst, bytes);
                 break;
             case BAMG_X_SLOTW:
+            case BAMG_X_SLOTW0:
                 if (!lv.slotw) fail(BAMG_EINVAL, "slot weights are kept only with options.collect on non-coarsest levels");
-                copy_out(lv.slotw, (size_t)rows * 4, dst, bytes);
+                // with one setup pass the first-pass weights are the final ones
+                copy_out(what == BAMG_X_SLOTW0 || o.setup_passes == 1 ? lv.slotw0 : lv.slotw, (size_t)rows * 4, dst,
+                         bytes);
                 break;
             default: fail(BAMG_EINVAL, "unknown export item %d", what);
         }

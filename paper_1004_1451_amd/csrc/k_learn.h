@@ -1,9 +1,11 @@
 // Learned form of the first-pass interpolation: the least-squares fit of
 // every F point (Algorithm 2) is computed as usual, its Gram and operator row
-// give the point's 24 features, the network (k_mlp.h) proposes weights for all
-// the point's slots, and the fit judges them: the proposal is kept when the
-// functional of eq. LSfuncrowi at the proposed weights is finite and at most
-// `judge` times the fit's own minimum; otherwise the fitted row is written.
+// give the point's 24 features, and the network (k_mlp.h) proposes a
+// correction to the fitted weights on all the point's slots, trained toward
+// the weights the method settles on after its recomputation pass.  The fit
+// judges the proposal: it is kept when the functional of eq. LSfuncrowi at the
+// corrected weights is finite and at most `judge` times the fit's own minimum;
+// otherwise the fitted row is written.
 #pragma once
 #include "k_mlp.h"
 #include "k_sparse.h"
@@ -73,7 +75,7 @@ k_ls_fit_learn(int n, const ChainGeo* __restrict__ geo, int nch, int Ru, const T
             bool finite = true;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                pm[s] = ((P.valid >> s) & 1) ? (double)S.y[w][l][s] : 0.0;
+                pm[s] = ((P.valid >> s) & 1) ? P.p[s] + (double)S.y[w][l][s] : 0.0;
                 finite &= isfinite(pm[s]);
             }
             double Lm = P.sigma;

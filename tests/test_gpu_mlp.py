@@ -97,10 +97,15 @@ def test_collected_features_match_oracle():
     F, *_ = M.level_features(U, O.tv_weights(Bl, U), Bl, g)
     Fg = h.export(0, B.X_FEATURES).reshape(ch.n, 24).astype(np.float64)
     assert np.abs(Fg - F).max() <= 1e-6 * max(1.0, np.abs(F).max())
-    # slot weights of the (here: only) fit equal the exported P
+    # the first pass's slot weights are the exported P (stopped after that pass)
     Pg, _ = _p_from_ell(h, 0, g.coarse().n)
-    assert np.array_equal(h.export(0, B.X_SLOTW).reshape(ch.n, 4).astype(np.float64),
+    assert np.array_equal(h.export(0, B.X_SLOTW0).reshape(ch.n, 4).astype(np.float64),
                           M.slot_weights(Pg, g).astype(np.float32).astype(np.float64))
+    # after a full setup the final slot weights are the final P
+    hf = B.Hierarchy.from_chain(ch, 8, B.default_options(levels=3, collect=1))
+    Pf, _ = _p_from_ell(hf, 0, g.coarse().n)
+    assert np.array_equal(hf.export(0, B.X_SLOTW).reshape(ch.n, 4).astype(np.float64),
+                          M.slot_weights(Pf, g).astype(np.float32).astype(np.float64))
 
 
 def test_judge_extremes():
@@ -116,18 +121,23 @@ def test_judge_extremes():
     for l in range(3):
         for what in (B.X_P_COL, B.X_P_VAL) if l < 2 else (B.X_B_VAL,):
             assert np.array_equal(h0.export(l, what), ls.export(l, what)), (l, what)
-    # judge 1e30: the level-0 rows are the network's own outputs on the valid slots
+    # judge 1e30: the level-0 rows are the fit plus the network's correction on
+    # every valid slot (the fit's weights come back rounded to FP32 here)
     h1 = B.Hierarchy.from_chain(ch, 8, B.default_options(**base, interp=B.INTERP_MLP, mlp_weights=th.data_ptr(),
                                                           mlp_judge=1e30))
     assert h1.stats().mlp_fallback == 0
     F = ls.export(0, B.X_FEATURES).reshape(ch.n, 24)
+    W0 = ls.export(0, B.X_SLOTW0).reshape(ch.n, 4).astype(np.float64)
     Y = B.mlp_forward(_dev(F), th).cpu().numpy().astype(np.float64)
     g = _grid(ch)
     Pg, _ = _p_from_ell(h1, 0, g.coarse().n)
     W = M.slot_weights(Pg, g)
     fpts = F[:, :4].sum(1) > 0
-    want = np.where(F[:, :4] > 0, Y, 0.0)
-    assert np.array_equal(W[fpts], want[fpts])
+    want = np.where(F[:, :4] > 0, W0 + Y, 0.0)
+    assert np.abs(W[fpts] - want[fpts]).max() <= 1e-6 * max(1.0, np.abs(want).max())
+    # and the fit's own weights are what the least-squares form writes
+    Pls, _ = _p_from_ell(ls, 0, g.coarse().n)
+    assert np.array_equal(M.slot_weights(Pls, g).astype(np.float32).astype(np.float64)[fpts], W0[fpts])
 
 
 def test_learned_setup_reaches_the_oracle_vector():
@@ -151,3 +161,35 @@ def test_bad_learned_options():
     with pytest.raises(B.BamgError) as e:
         B.Hierarchy.from_chain(ch, 4, B.default_options(levels=2, setup_passes=3))
     assert e.value.code == B.EINVAL
+
+
+def test_trained_network_gain_is_measured(record_property):
+    # small version of the learned workload: train on jittered tandems, then
+    # measure what the network changes on a held-out chain (reported, whatever
+    # its sign): the distance of the level-0 weights to the final fit, and the
+    # cycles and fallback share of the one-pass learned setup
+    from paper_1004_1451_amd import learned as LRN
+    chains = C.training_chains(6, n_min=63, n_max=127)
+    params, info, sizes = LRN.train(chains, r=8, levels=4, n_val=2, epochs=4, batch=1024)
+    assert sizes[0] > 10000 and sizes[1] > 1000
+    assert info.val_loss_last < info.val_loss_first
+    ev = C.tandem_queue(95, jitter=0.2, seed=7, chain_id=5)
+    hf = B.Hierarchy.from_chain(ev, 8, B.default_options(levels=4, collect=1))
+    F = hf.export(0, B.X_FEATURES).reshape(ev.n, 24)
+    Tfin = hf.export(0, B.X_SLOTW).reshape(ev.n, 4).astype(np.float64)
+    T1 = hf.export(0, B.X_SLOTW0).reshape(ev.n, 4).astype(np.float64)
+    Y = B.mlp_forward(_dev(F), params).cpu().numpy().astype(np.float64)
+    m = F[:, :4] > 0
+    f = m.sum(1) > 0
+    err_fit = np.sqrt(((T1 - Tfin)[f] ** 2).mean())
+    err_net = np.sqrt(((np.where(m, T1 + Y, 0.0) - Tfin)[f] ** 2).mean())
+    res = {}
+    for name, kw in (("ls_1pass", {}), ("learned_1pass", dict(interp=B.INTERP_MLP, mlp_weights=params.data_ptr()))):
+        x, inf, h = B.stationary(ev, 8, tol=1e-10, max_cycles=300, levels=4, setup_passes=1, **kw)
+        assert inf.converged
+        st = h.stats()
+        res[name] = (inf.cycles, st.mlp_fallback / max(1, st.mlp_points))
+    record_property("level0_weight_rms_to_final_fit", {"first_pass_fit": err_fit, "network": err_net})
+    record_property("cycles_and_fallback", res)
+    print("gain: weight rms to final fit %.5f (fit) -> %.5f (network); %s" % (err_fit, err_net, res))
+    assert err_net <= 1.5 * err_fit          # the correction never wrecks the fit
