@@ -39,7 +39,7 @@ def _traffic_from_profiles(name: str):
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_1004_1451_amd", "csrc", "k_sparse.h")
+    src = os.path.join(ROOT, "paper_1004_1451_amd", "csrc", "k_sweep.h")
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     if vals.get("source_hash") != h:
         return None          # kernel changed since the counters were taken
@@ -51,13 +51,13 @@ def _traffic_from_profiles(name: str):
 
 def cpu_baseline(args):
     """The oracle, untuned, on a bounded sample: the whole method on the
-    tandem queue N = 767 (n = 589,824; the same 6 levels, r, rates and
+    tandem queue N = 1023 (n = 1,048,576; the same 6 levels, r, rates and
     tolerance), scaled to n = 4,194,304 by the ratio of state counts (the
     work per level is linear in n).  BLAS limited to one thread."""
     from threadpoolctl import threadpool_limits
     from oracle import bamg_oracle as O
     from paper_1004_1451_amd import chains as C
-    ch = C.tandem_queue(767)
+    ch = C.tandem_queue(1023)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         x, info, _ = O.stationary(ch.to_scipy(), O.Grid(ch.nx, ch.ny, ch.periodic), args.r,
@@ -65,7 +65,7 @@ def cpu_baseline(args):
         dt = time.perf_counter() - t0
     scale = 4194304 / ch.n
     return {"value": dt * scale, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle setup+solve on tandem N=767 (n={ch.n:,}, {args.levels} levels, r={args.r}, "
+            "sample": f"oracle setup+solve on tandem N=1023 (n={ch.n:,}, {args.levels} levels, r={args.r}, "
                       f"tol={args.tol:g}, {info.cycles} cycles) took {dt:.2f} s on 1 thread; scaled by n ratio "
                       f"{scale:.2f}",
             "converged": bool(info.converged)}

@@ -83,7 +83,7 @@ typedef struct {
     int32_t caliber;     /* c: max interpolatory points per fine point        */
     int32_t n_eig;       /* k: coarsest eigenpairs including the null vector  */
     int32_t arnoldi_m;   /* Krylov dimension of the coarsest eigensolve       */
-    int32_t gmres_m;     /* restart length of flexible GMRES                   */
+    int32_t gmres_m;     /* restart length of flexible GMRES (1 .. 63)         */
     int32_t precision;   /* BAMG_FP64 or BAMG_MIXED                            */
     int32_t interp;      /* BAMG_INTERP_LS or BAMG_INTERP_MLP                  */
     const float* mlp_weights; /* device, BAMG_MLP_NPARAM floats; needed for MLP */
@@ -134,7 +134,7 @@ typedef struct {
                                            time and GPU time                 */
     int32_t sweep_vw, sweep_bs; /* launch shape of the level-0 multi-vector sweep:
                                    columns per thread, threads per workgroup
-                                   (autotuned once per shape and process;
+                                   (VW 1, 2, 3, 4, 6 or 12; autotuned once per shape and process;
                                    BAMG_SWEEP_VARIANT="VW,BS" forces one)    */
     double tune_ms;         /* process total spent timing sweep candidates    */
     int64_t mlp_points;     /* learned form: F points judged (all levels)      */

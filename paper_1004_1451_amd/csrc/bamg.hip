@@ -70,7 +70,7 @@ inline int nblk(long long n) { return (int)std::max<long long>(1, (n + BAMG_BLK 
 // Per-chain reductions split each chain into chunks of SEG_ROWS rows, so that
 // a large chain fills the chip and a chain's summation order does not depend
 // on the other chains of its batch.
-constexpr int SEG_ROWS = 4096;
+constexpr int SEG_ROWS = 1024;
 // The TV-weight and Rayleigh partials do a sparse product per (row, column)
 // on top of the sum: shorter chunks keep many workgroups in flight.
 constexpr int CN_ROWS = 256;
@@ -195,7 +195,9 @@ bool forced_sweep_shape(int R, SweepShape& out) {
     if (!e || !*e) return false;
     int vw = 0, bs = 0;
     if (sscanf(e, "%d,%d", &vw, &bs) != 2) return false;
-    if ((vw != 1 && vw != 2 && vw != 4) || (bs != 128 && bs != 256 && bs != 512) || R % vw) return false;
+    if ((vw != 1 && vw != 2 && vw != 3 && vw != 4 && vw != 6 && vw != 12) || (bs != 128 && bs != 256 && bs != 512) ||
+        ((vw == 3 || vw > 4) && bs > 256) || R % vw)
+        return false;
     out.vw = vw;
     out.bs = bs;
     return true;
@@ -341,9 +343,11 @@ struct Engine : bamg_ctx {
     T* sweep_tmp = nullptr;
     // FGMRES
     int m_alloc = 0;
+    double* hbuf2 = nullptr;
     double *Vk = nullptr, *Zk = nullptr, *wk = nullptr, *Hg = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr,
            *ysol = nullptr, *hbuf = nullptr, *rvec = nullptr, *est = nullptr, *xperm = nullptr;
     int *act = nullptr, *kd = nullptr, *act2 = nullptr;
+    int* cmask = nullptr;            // chains the cycle works on (nch > 1; all ones outside solve)
     double *vin = nullptr, *vout = nullptr;   // permuted vectors of bamg_apply_vcycle
     // graph of one cycle on fixed buffers
     hipGraph_t graph = nullptr;
@@ -584,6 +588,9 @@ struct Engine : bamg_ctx {
         zero(kind, sizeof(int) * nch * KV);
         zero(ent_col, sizeof(int) * nch * KV);
         x0 = A.alloc<double>(n);
+        if (nch > 1) {
+            cmask = A.upload(std::vector<int>(nch, 1));
+        }
         {
             const size_t P = L[0].segp;
             size_t need = 4096;
@@ -657,6 +664,12 @@ struct Engine : bamg_ctx {
             case 4128: sweep_launch<4, 128>(rows, R, Bm, dinv, X, F, Y); break;
             case 4256: sweep_launch<4, 256>(rows, R, Bm, dinv, X, F, Y); break;
             case 4512: sweep_launch<4, 512>(rows, R, Bm, dinv, X, F, Y); break;
+            case 3128: sweep_launch<3, 128>(rows, R, Bm, dinv, X, F, Y); break;
+            case 3256: sweep_launch<3, 256>(rows, R, Bm, dinv, X, F, Y); break;
+            case 6128: sweep_launch<6, 128>(rows, R, Bm, dinv, X, F, Y); break;
+            case 6256: sweep_launch<6, 256>(rows, R, Bm, dinv, X, F, Y); break;
+            case 12128: sweep_launch<12, 128>(rows, R, Bm, dinv, X, F, Y); break;
+            case 12256: sweep_launch<12, 256>(rows, R, Bm, dinv, X, F, Y); break;
             default: fail(BAMG_EDEVICE, "no sweep variant %d,%d", sh.vw, sh.bs);
         }
     }
@@ -682,9 +695,9 @@ struct Engine : bamg_ctx {
         }
         auto t0 = std::chrono::steady_clock::now();
         std::vector<SweepShape> cand;
-        for (int vw : {1, 2, 4})
+        for (int vw : {1, 2, 3, 4, 6, 12})
             for (int bs : {128, 256, 512})
-                if (R % vw == 0) cand.push_back({vw, bs});
+                if (R % vw == 0 && (vw == 1 || vw == 2 || vw == 4 || bs <= 256)) cand.push_back({vw, bs});
         hipEvent_t a, b;
         HIPCHK(hipEventCreate(&a));
         HIPCHK(hipEventCreate(&b));
@@ -1112,12 +1125,13 @@ struct Engine : bamg_ctx {
             int maxn = 0;
             for (int c = c0; c < c1; ++c) maxn = std::max(maxn, cdh[c].n);
             const dim3 gw(ceil_div(maxn, 4), c1 - c0);
+            const int* am = cmask ? cmask + c0 : nullptr;
             if (MIXED)
                 hipLaunchKernelGGL(k_cz_gemv_f32, gw, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)(cd + c0),
-                                   (const float*)Wfp, (const float*)lv.f, (float*)lv.e);
+                                   (const float*)Wfp, (const float*)lv.f, (float*)lv.e, am);
             else
                 hipLaunchKernelGGL(k_cz_gemv_rows, gw, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)(cd + c0),
-                                   (const double*)Wp, (const double*)lv.f, (double*)lv.e);
+                                   (const double*)Wp, (const double*)lv.f, (double*)lv.e, am);
             HIPCHK(hipGetLastError());
         }
         if (lv.ncont == 0) return;
@@ -1127,26 +1141,27 @@ struct Engine : bamg_ctx {
         T* cur = lv.zero_into_e2 ? lv.e2 : lv.e;
         T* oth = lv.zero_into_e2 ? lv.e : lv.e2;
         const int nb = nblk(rows);
+        const RowMask mk{lv.dgeo, lv.ncont, cmask};     // continuing chains' rows
         if (o.nu_pre > 0) {
-            LAUNCH((k_jacobi_zero<T, T>), nb, BAMG_BLK, s, rows, (const T*)lv.dinv, (const T*)lv.f, cur);
+            LAUNCH((k_jacobi_zero<T, T>), nb, BAMG_BLK, s, rows, (const T*)lv.dinv, (const T*)lv.f, cur, mk);
             for (int k = 1; k < o.nu_pre; ++k) {
                 LAUNCH((k_sweep<T, T>), nb, BAMG_BLK, s, rows, 1, d1, lv.B.rp, lv.B.ci, (const T*)lv.B.v,
-                       (const T*)lv.dinv, (const T*)cur, (const T*)lv.f, oth);
+                       (const T*)lv.dinv, (const T*)cur, (const T*)lv.f, oth, mk);
                 std::swap(cur, oth);
             }
         } else {
-            LAUNCH((k_fill_t<T>), nb, BAMG_BLK, s, rows, cur);
+            LAUNCH((k_fill_t<T>), nb, BAMG_BLK, s, rows, cur, mk);
         }
         LAUNCH((k_residual<T, T>), nb, BAMG_BLK, s, rows, lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const T*)cur,
-               (const T*)lv.f, lv.r);
+               (const T*)lv.f, lv.r, mk);
         LAUNCH(k_restrict_box<T>, nblk(c.rows), BAMG_BLK, s, c.rows, (const ChainGeo*)c.dgeo,
                (const ChainGeo*)lv.dgeo, c.nch, (const unsigned short*)lv.qmask, (const unsigned char*)lv.jcnt,
-               (const T*)lv.r, c.f);
+               (const T*)lv.r, c.f, (const int*)cmask);
         vcycle(l + 1);
-        LAUNCH((k_prolong_add<T, T>), nb, BAMG_BLK, s, rows, lv.pc, (const T*)lv.pv, (const T*)c.e, cur);
+        LAUNCH((k_prolong_add<T, T>), nb, BAMG_BLK, s, rows, lv.pc, (const T*)lv.pv, (const T*)c.e, cur, mk);
         for (int k = 0; k < o.nu_post; ++k) {
             LAUNCH((k_sweep<T, T>), nb, BAMG_BLK, s, rows, 1, d1, lv.B.rp, lv.B.ci, (const T*)lv.B.v,
-                   (const T*)lv.dinv, (const T*)cur, (const T*)lv.f, oth);
+                   (const T*)lv.dinv, (const T*)cur, (const T*)lv.f, oth, mk);
             std::swap(cur, oth);
         }
         if (cur != lv.e) fail(BAMG_EDEVICE, "cycle buffer parity");
@@ -1227,6 +1242,11 @@ struct Engine : bamg_ctx {
 
     // Caller's chain order in and out (the handle's rows are depth-sorted).
     void vcycle_apply(const double* f, double* e) override {
+        if (cmask) {
+            std::vector<int> ones(nch, 1);
+            HIPCHK(hipMemcpyAsync(cmask, ones.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
+            sync();
+        }
         if (!reordered) {
             precondition(f, e);
         } else {
@@ -1266,8 +1286,9 @@ struct Engine : bamg_ctx {
             g = A.alloc<double>((size_t)nch * GS);
             ysol = A.alloc<double>((size_t)nch * GS);
             hbuf = A.alloc<double>((size_t)nch * GS);
+            hbuf2 = A.alloc<double>((size_t)nch * GS);
             est = A.alloc<double>(nch);
-            act = A.alloc<int>(nch);
+            act = cmask ? cmask : A.alloc<int>(nch);
             act2 = A.alloc<int>(nch);
             kd = A.alloc<int>(nch);
             if (reordered) xperm = A.alloc<double>(N);
@@ -1294,7 +1315,8 @@ struct Engine : bamg_ctx {
         std::vector<double> rel(nch, 0.0);
         for (;;) {
             // r = -B x; per-chain relative 1-norm residual
-            LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)xi, -1.0, rvec);
+            LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)xi, -1.0, rvec,
+                   RowMask{g0, nch, nullptr});
             seg_reduce<RED_ABS>(rvec, nullptr, sc + 1);
             seg_reduce<RED_ABS>(xi, nullptr, sc + 2);
             seg_reduce<RED_DOT>(rvec, rvec, sc + 3);
@@ -1327,25 +1349,42 @@ struct Engine : bamg_ctx {
             for (int j = 0; j < m && inf.cycles < max_cycles; ++j) {
                 double* vj = Vk + (size_t)j * N;
                 double* zj = Zk + (size_t)j * N;
+                // once most chains have stopped, the masked cycle is little
+                // work in many launches: replay it from a graph instead
+                if (nch > 1 && o.cycle_mode == 0 && cycle_decided && !use_graph) {
+                    long long act_rows = 0;
+                    for (int c = 0; c < nch; ++c) act_rows += hact[c] ? chains[c].n : 0;
+                    if (4 * act_rows < n) { use_graph = true; st.cycle_graph = 1; }
+                }
                 precondition(vj, zj);
                 ++inf.cycles;
-                LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)zj, 1.0, wk);
-                // classical Gram-Schmidt, second pass only where needed
-                for (int pass = 0; pass < 2; ++pass) {
-                    const int* am = pass == 0 ? act : act2;
-                    const int nv = pass == 0 ? j + 2 : j + 1;       // pass 0 also forms ||w||^2
-                    hipLaunchKernelGGL(k_seg_mdot_partial, dim3(L[0].segp, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS,
-                                       N, j + 1, nv, am, (const double*)Vk, (const double*)wk, part);
-                    hipLaunchKernelGGL(k_seg_mdot_final, dim3(nv, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS,
-                                       L[0].segp, j + 1, nv, am, (const double*)part, hbuf, GS, Hg + (size_t)j * ld,
-                                       HSg);
-                    HIPCHK(hipGetLastError());
-                    LAUNCH(k_seg_vupdate, nb, BAMG_BLK, s, N, g0, nch, j + 1, am, (const double*)Vk,
-                           (const double*)hbuf, GS, wk);
-                    if (pass == 0)
-                        LAUNCH(k_seg_dgks, ceil_div(nch, 64), 64, s, nch, j + 1, act, (const double*)hbuf, GS, act2);
+                LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)zj, 1.0, wk,
+                       RowMask{g0, nch, cmask});
+                // classical Gram-Schmidt: first-pass dots (and ||w||^2), then
+                // the fused update + second-pass dots, then the second update
+                // where the first pass lost over half of ||w||^2, fused with
+                // the new norm
+                const int P0 = L[0].segp;
+                const dim3 gsg(P0, nch);
+                hipLaunchKernelGGL(k_seg_mdot_partial, gsg, dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, N, j + 1, j + 2,
+                                   (const int*)act, (const double*)Vk, (const double*)wk, part);
+                hipLaunchKernelGGL(k_seg_mdot_final, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0, j + 1,
+                                   j + 2, (const int*)act, (const double*)part, hbuf, GS, Hg + (size_t)j * ld, HSg);
+                HIPCHK(hipGetLastError());
+                LAUNCH(k_seg_dgks, ceil_div(nch, 64), 64, s, nch, j + 1, act, (const double*)hbuf, GS, act2);
+                {
+                    auto kd_ = j + 1 <= 8 ? k_seg_upd_dots<8>
+                             : j + 1 <= 16 ? k_seg_upd_dots<16> : j + 1 <= 32 ? k_seg_upd_dots<32> : k_seg_upd_dots<64>;
+                    hipLaunchKernelGGL(kd_, gsg, dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, N, j + 1, (const int*)act,
+                                       (const double*)Vk, (const double*)hbuf, GS, wk, part);
                 }
-                seg_reduce<RED_DOT>(wk, wk, sc + 4);
+                hipLaunchKernelGGL(k_seg_mdot_final, dim3(j + 1, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0, j + 1,
+                                   j + 1, (const int*)act2, (const double*)part, hbuf2, GS, Hg + (size_t)j * ld, HSg);
+                hipLaunchKernelGGL(k_seg_upd_norm, gsg, dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, N, j + 1, (const int*)act,
+                                   (const int*)act2, (const double*)Vk, (const double*)hbuf2, GS, wk, part);
+                hipLaunchKernelGGL(k_seg_wave_final, dim3(nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0,
+                                   (const int*)act, (const double*)part, sc + 4, SCS);
+                HIPCHK(hipGetLastError());
                 LAUNCH(k_seg_scale, nb, BAMG_BLK, s, N, g0, nch, (const int*)act, (const double*)wk,
                        (const double*)nullptr, (const double*)(sc + 4), SCS, 1, Vk + (size_t)(j + 1) * N);
                 LAUNCH(k_seg_givens, ceil_div(nch, 64), 64, s, nch, j, ld, (const int*)act, Hg, HSg,
@@ -1374,7 +1413,8 @@ struct Engine : bamg_ctx {
         seg_reduce<RED_NEGSUM>(xi, nullptr, sc + 5);
         LAUNCH(k_clamp, nb, BAMG_BLK, s, N, xi);
         normalise();
-        LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)xi, -1.0, rvec);
+        LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)xi, -1.0, rvec,
+               RowMask{g0, nch, nullptr});
         seg_reduce<RED_ABS>(rvec, nullptr, sc + 1);
         seg_reduce<RED_ABS>(xi, nullptr, sc + 2);
         if (reordered) {
@@ -1506,7 +1546,7 @@ int run_guarded(const std::function<void()>& fn) {
 
 void check_options(const bamg_options& o) {
     if (o.nu_setup < 0 || o.nu_pre < 0 || o.nu_post < 0 || !(o.omega > 0) || o.caliber < 1 || o.n_eig < 1 ||
-        o.n_eig > 8 || o.gmres_m < 1 || o.gmres_m > 200 || o.arnoldi_m < 1 || o.levels < 0 || o.coarse_max < 1)
+        o.n_eig > 8 || o.gmres_m < 1 || o.gmres_m > GS_MAXB - 1 || o.arnoldi_m < 1 || o.levels < 0 || o.coarse_max < 1)
         fail(BAMG_EINVAL, "invalid options");
     if (o.cycle_mode < 0 || o.cycle_mode > 2) fail(BAMG_EINVAL, "cycle_mode %d not in {0, 1, 2}", o.cycle_mode);
     if (o.interp != BAMG_INTERP_LS && o.interp != BAMG_INTERP_MLP)
@@ -1900,7 +1940,8 @@ int bamg_relax(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const 
         FastDiv dR((uint32_t)R);
         for (int k = 0; k < nu; ++k) {
             LAUNCH((k_sweep<double, double>), nblk((long long)N * R), BAMG_BLK, s, N, R, dR, (const int*)brp,
-                   (const int*)bci, (const double*)bv, (const double*)dinv, (const double*)a, F, b);
+                   (const int*)bci, (const double*)bv, (const double*)dinv, (const double*)a, F, b,
+                   RowMask{(const ChainGeo*)dg, 1, nullptr});
             std::swap(a, b);
         }
         if (a != X) HIPCHK(hipMemcpyAsync(X, a, sizeof(double) * N * R, hipMemcpyDeviceToDevice, s));

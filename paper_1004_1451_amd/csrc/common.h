@@ -95,3 +95,30 @@ __device__ __forceinline__ int find_chain(const ChainGeo* __restrict__ g, int nc
     }
     return lo;
 }
+
+// Chain mask of the batched cycle: a workgroup whose rows [r0, r1] belong only
+// to chains with act[c] == 0 has nothing to do (act == nullptr: every chain is
+// active).  The result is the same for every thread of the workgroup.
+struct RowMask {
+    const ChainGeo* geo;
+    int nch;
+    const int* act;
+};
+
+__device__ __forceinline__ bool rows_active(const RowMask& m, int r0, int r1) {
+    if (!m.act) return true;
+    const int c0 = find_chain(m.geo, m.nch, r0), c1 = find_chain(m.geo, m.nch, r1);
+    for (int c = c0; c <= c1; ++c)
+        if (m.act[c]) return true;
+    return false;
+}
+
+// Rows [tile * blk / R, ((tile + 1) * blk - 1) / R] of an n-row operator
+// handled by workgroup `tile` of a thread-per-(row, column) kernel.
+__device__ __forceinline__ bool tile_active(const RowMask& m, int tile, int blk, int R, int n) {
+    if (!m.act) return true;
+    const long long t0 = (long long)tile * blk;
+    const int r0 = (int)(t0 / R);
+    const int r1 = (int)min((long long)n - 1, (t0 + blk - 1) / R);
+    return r0 < n && rows_active(m, r0, r1);
+}

@@ -488,7 +488,8 @@ k_cz_gemv(const CoarseDesc* __restrict__ cd, int which, const double* __restrict
 // the level's FP32 cycle buffer at row0).
 __global__ void __launch_bounds__(BAMG_BLK)
 k_cz_gemv_f32(const CoarseDesc* __restrict__ cd, const float* __restrict__ Wp, const float* __restrict__ x,
-              float* __restrict__ out) {
+              float* __restrict__ out, const int* __restrict__ act) {
+    if (act && !act[blockIdx.y]) return;
     const CoarseDesc d = cd[blockIdx.y];
     const float* W = Wp + d.woff;
     const int lane = threadIdx.x % BAMG_WAVE;
@@ -505,7 +506,8 @@ k_cz_gemv_f32(const CoarseDesc* __restrict__ cd, const float* __restrict__ Wp, c
 // FP64 coarse solve inside the cycle: e[row0 + i] = sum_j W[i, j] f[row0 + j].
 __global__ void __launch_bounds__(BAMG_BLK)
 k_cz_gemv_rows(const CoarseDesc* __restrict__ cd, const double* __restrict__ Wp, const double* __restrict__ x,
-               double* __restrict__ out) {
+               double* __restrict__ out, const int* __restrict__ act) {
+    if (act && !act[blockIdx.y]) return;
     const CoarseDesc d = cd[blockIdx.y];
     const double* W = Wp + d.woff;
     const int lane = threadIdx.x % BAMG_WAVE;

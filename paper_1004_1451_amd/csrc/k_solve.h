@@ -327,6 +327,92 @@ __global__ void k_seg_dgks(int nch, int nb, const int* __restrict__ act, const d
     act2[c] = need;
 }
 
+// Fused Gram-Schmidt passes over a row chunk of each chain (chunk and wave
+// partials in the layout of k_seg_mdot_partial).
+// k_seg_upd_dots: w <- w - sum_{b<nb} h_b V_b on chains with act, then the
+// dots <V_b, w> of the updated w (the second pass's coefficients): each row's
+// V values are loaded once into registers and serve the update and the dots.
+// MAXB (>= nb) values and accumulators per thread, in registers.
+#define GS_MAXB 64
+template <int MAXB>
+__global__ void __launch_bounds__(BAMG_BLK)
+k_seg_upd_dots(const ChainGeo* __restrict__ geo, int seg_rows, int N, int nb, const int* __restrict__ act,
+               const double* __restrict__ V, const double* __restrict__ h, int HS, double* __restrict__ w,
+               double* __restrict__ part) {
+    const ChainGeo g = geo[blockIdx.y];
+    if (!act[blockIdx.y]) return;
+    const int lane = threadIdx.x % BAMG_WAVE, wv = threadIdx.x / BAMG_WAVE;
+    const int i0 = g.off + blockIdx.x * seg_rows, i1 = min(g.off + g.n, i0 + seg_rows);
+    if (i0 >= i1) return;
+    const double* hc = h + (size_t)blockIdx.y * HS;
+    double acc[MAXB];
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) acc[b] = 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += BAMG_BLK) {
+        double v[MAXB];
+#pragma unroll
+        for (int b = 0; b < MAXB; ++b) v[b] = b < nb ? V[(size_t)b * N + i] : 0.0;
+        double s = w[i];
+#pragma unroll
+        for (int b = 0; b < MAXB; ++b)
+            if (b < nb) s -= hc[b] * v[b];
+        w[i] = s;
+#pragma unroll
+        for (int b = 0; b < MAXB; ++b)
+            if (b < nb) acc[b] += v[b] * s;
+    }
+    const size_t slot = (((size_t)blockIdx.y * gridDim.x + blockIdx.x) * (BAMG_BLK / BAMG_WAVE) + wv) * nb;
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+        if (b < nb) {
+            const double t = wave_sum(acc[b]);
+            if (lane == 0) part[slot + b] = t;
+        }
+    }
+}
+
+// k_seg_upd_norm: w <- w - sum_{b<nb} h_b V_b on chains with act2 (the second
+// pass where it is needed), then the partial ||w||^2 of every chain with act
+// (one value per wave, nv = 1 layout).
+__global__ void __launch_bounds__(BAMG_BLK)
+k_seg_upd_norm(const ChainGeo* __restrict__ geo, int seg_rows, int N, int nb, const int* __restrict__ act,
+               const int* __restrict__ act2, const double* __restrict__ V, const double* __restrict__ h, int HS,
+               double* __restrict__ w, double* __restrict__ part) {
+    const ChainGeo g = geo[blockIdx.y];
+    if (!act[blockIdx.y]) return;
+    const bool upd = act2[blockIdx.y] != 0;
+    const int lane = threadIdx.x % BAMG_WAVE, wv = threadIdx.x / BAMG_WAVE;
+    const int i0 = g.off + blockIdx.x * seg_rows, i1 = min(g.off + g.n, i0 + seg_rows);
+    if (i0 >= i1) return;
+    const double* hc = h + (size_t)blockIdx.y * HS;
+    double acc = 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += BAMG_BLK) {
+        double s = w[i];
+        if (upd) {
+            for (int b = 0; b < nb; ++b) s -= hc[b] * V[(size_t)b * N + i];
+            w[i] = s;
+        }
+        acc += s * s;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * (BAMG_BLK / BAMG_WAVE) + wv] = acc;
+}
+
+// out[c * stride] = sum of chain c's wave partials (its own chunk count, P
+// chunks per chain) for chains with act; one block per chain.
+__global__ void k_seg_wave_final(const ChainGeo* __restrict__ geo, int seg_rows, int P, const int* __restrict__ act,
+                                 const double* __restrict__ part, double* __restrict__ out, int stride) {
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    const int c = blockIdx.x;
+    if (!act[c]) return;
+    const int WPB = BAMG_BLK / BAMG_WAVE;
+    const int np = ((geo[c].n + seg_rows - 1) / seg_rows) * WPB;
+    double s = 0;
+    for (int j = threadIdx.x; j < np; j += BAMG_BLK) s += part[(size_t)c * P * WPB + j];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[(size_t)c * stride] = s;
+}
+
 // w -= sum_b h_b V_b on the rows of active chains.
 __global__ void k_seg_vupdate(int N, const ChainGeo* __restrict__ geo, int nch, int nv, const int* __restrict__ act,
                               const double* __restrict__ V, const double* __restrict__ h, int HS,
@@ -458,7 +544,8 @@ __global__ void k_seg_csr_fill(const int* __restrict__ src_off, const int* __res
 
 // e = 0 (a fill kernel, so that a captured cycle holds no memset node).
 template <typename T>
-__global__ void k_fill_t(int n, T* __restrict__ e) {
+__global__ void k_fill_t(int n, T* __restrict__ e, RowMask mk) {
+    if (!tile_active(mk, blockIdx.x, BAMG_BLK, 1, n)) return;
     int i = blockIdx.x * BAMG_BLK + threadIdx.x;
     if (i < n) e[i] = (T)0;
 }

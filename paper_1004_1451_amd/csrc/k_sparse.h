@@ -9,6 +9,7 @@
 //   Q_l      : ELL-9, slot s of coarse row I at 9I+s, fine columns ascending.
 #pragma once
 #include "common.h"
+#include "k_sweep.h"
 
 enum : int {
     ERR_RANGE = 1,      // column index out of range / not ascending / bad row_ptr
@@ -179,28 +180,6 @@ __global__ void k_scan_add(int n, int* __restrict__ out, const int* __restrict__
 // value loads are issued four at a time before the dependent X loads, so a
 // row costs two memory round trips instead of two per entry; padding slots
 // add an exact zero, so the result equals the plain sequential sum.
-template <typename T, typename M>
-__device__ __forceinline__ T row_dot(int p0, int p1, const int* __restrict__ ci, const M* __restrict__ v,
-                                     const T* __restrict__ X, int R, int k, int self) {
-    T acc = 0;
-    for (int p = p0; p < p1; p += 4) {
-        int c[4];
-        M w[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            bool ok = p + u < p1;
-            c[u] = ok ? ci[p + u] : self;
-            w[u] = ok ? v[p + u] : (M)0;
-        }
-        T x[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) x[u] = X[(size_t)c[u] * R + k];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc += (T)w[u] * x[u];
-    }
-    return acc;
-}
-
 // X_out = X_in + dinv (F - B X_in) on R interleaved columns (omega-Jacobi,
 // Section 3).  One thread per (row, column); a wavefront covers 64/R rows and
 // every stencil offset reads a contiguous run of X.  F == nullptr: homogeneous.
@@ -208,8 +187,10 @@ template <typename T, typename M>
 __global__ void __launch_bounds__(BAMG_BLK)
 k_sweep(int n, int R, FastDiv divR, const int* __restrict__ rp, const int* __restrict__ ci,
         const M* __restrict__ v, const M* __restrict__ dinv, const T* __restrict__ X,
-        const T* __restrict__ F, T* __restrict__ Y) {
-    int t = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+        const T* __restrict__ F, T* __restrict__ Y, RowMask mk) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (!tile_active(mk, tile, BAMG_BLK, R, n)) return;
+    int t = tile * BAMG_BLK + threadIdx.x;
     if (t >= n * R) return;
     int i = (int)divR.div((uint32_t)t), k = t - i * R;
     const T xt = X[t];
@@ -219,98 +200,13 @@ k_sweep(int n, int R, FastDiv divR, const int* __restrict__ rp, const int* __res
     Y[t] = xt + d * (f - acc);
 }
 
-// Vector forms of the sweep for the autotuner: a thread owns VW adjacent
-// columns of one row (G = R / VW threads per row) and moves them with 8- or
-// 16-byte loads; blocks of BS threads.  Same arithmetic per entry as k_sweep
-// (products added in CSR order), so every variant gives the same bits.
-template <typename T, int VW>
-struct VecIO;
-template <> struct VecIO<double, 1> {
-    static __device__ __forceinline__ void ld(const double* p, double* x) { x[0] = *p; }
-    static __device__ __forceinline__ void st(double* p, const double* x) { *p = x[0]; }
-};
-template <> struct VecIO<double, 2> {
-    static __device__ __forceinline__ void ld(const double* p, double* x) {
-        const double2 v = *(const double2*)p; x[0] = v.x; x[1] = v.y;
-    }
-    static __device__ __forceinline__ void st(double* p, const double* x) { *(double2*)p = make_double2(x[0], x[1]); }
-};
-template <> struct VecIO<double, 4> {
-    static __device__ __forceinline__ void ld(const double* p, double* x) {
-        const double2 a = ((const double2*)p)[0], b = ((const double2*)p)[1];
-        x[0] = a.x; x[1] = a.y; x[2] = b.x; x[3] = b.y;
-    }
-    static __device__ __forceinline__ void st(double* p, const double* x) {
-        ((double2*)p)[0] = make_double2(x[0], x[1]);
-        ((double2*)p)[1] = make_double2(x[2], x[3]);
-    }
-};
-template <> struct VecIO<float, 1> {
-    static __device__ __forceinline__ void ld(const float* p, float* x) { x[0] = *p; }
-    static __device__ __forceinline__ void st(float* p, const float* x) { *p = x[0]; }
-};
-template <> struct VecIO<float, 2> {
-    static __device__ __forceinline__ void ld(const float* p, float* x) {
-        const float2 v = *(const float2*)p; x[0] = v.x; x[1] = v.y;
-    }
-    static __device__ __forceinline__ void st(float* p, const float* x) { *(float2*)p = make_float2(x[0], x[1]); }
-};
-template <> struct VecIO<float, 4> {
-    static __device__ __forceinline__ void ld(const float* p, float* x) {
-        const float4 v = *(const float4*)p; x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
-    }
-    static __device__ __forceinline__ void st(float* p, const float* x) {
-        *(float4*)p = make_float4(x[0], x[1], x[2], x[3]);
-    }
-};
-
-template <typename T, typename M, int VW, int BS>
-__global__ void __launch_bounds__(BS)
-k_sweep_v(int n, int G, FastDiv divG, const int* __restrict__ rp, const int* __restrict__ ci,
-          const M* __restrict__ v, const M* __restrict__ dinv, const T* __restrict__ X,
-          const T* __restrict__ F, T* __restrict__ Y) {
-    const int t = xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
-    if (t >= n * G) return;
-    const int i = (int)divG.div((uint32_t)t), kg = t - i * G;
-    const int R = G * VW;
-    const size_t base = (size_t)i * R + (size_t)kg * VW;
-    T xt[VW], f[VW], acc[VW];
-    VecIO<T, VW>::ld(X + base, xt);
-    if (F) VecIO<T, VW>::ld(F + base, f);
-    else
-#pragma unroll
-        for (int q = 0; q < VW; ++q) f[q] = (T)0;
-#pragma unroll
-    for (int q = 0; q < VW; ++q) acc[q] = (T)0;
-    const T d = (T)dinv[i];
-    const int p0 = rp[i], p1 = rp[i + 1];
-    for (int p = p0; p < p1; p += 4) {
-        int c[4];
-        M w[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const bool ok = p + u < p1;
-            c[u] = ok ? ci[p + u] : i;
-            w[u] = ok ? v[p + u] : (M)0;
-        }
-        T x[4][VW];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) VecIO<T, VW>::ld(X + (size_t)c[u] * R + (size_t)kg * VW, x[u]);
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int q = 0; q < VW; ++q) acc[q] += (T)w[u] * x[u][q];
-    }
-    T y[VW];
-#pragma unroll
-    for (int q = 0; q < VW; ++q) y[q] = xt[q] + d * (f[q] - acc[q]);
-    VecIO<T, VW>::st(Y + base, y);
-}
-
 // First smoothing sweep from a zero guess: e = dinv * f.
 template <typename T, typename M>
-__global__ void k_jacobi_zero(int n, const M* __restrict__ dinv, const T* __restrict__ f, T* __restrict__ e) {
-    int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+__global__ void k_jacobi_zero(int n, const M* __restrict__ dinv, const T* __restrict__ f, T* __restrict__ e,
+                              RowMask mk) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (!tile_active(mk, tile, BAMG_BLK, 1, n)) return;
+    int i = tile * BAMG_BLK + threadIdx.x;
     if (i < n) e[i] = (T)dinv[i] * f[i];
 }
 
@@ -318,8 +214,10 @@ __global__ void k_jacobi_zero(int n, const M* __restrict__ dinv, const T* __rest
 template <typename T, typename M>
 __global__ void __launch_bounds__(BAMG_BLK)
 k_residual(int n, const int* __restrict__ rp, const int* __restrict__ ci, const M* __restrict__ v,
-           const T* __restrict__ e, const T* __restrict__ f, T* __restrict__ r) {
-    int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+           const T* __restrict__ e, const T* __restrict__ f, T* __restrict__ r, RowMask mk) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (!tile_active(mk, tile, BAMG_BLK, 1, n)) return;
+    int i = tile * BAMG_BLK + threadIdx.x;
     if (i >= n) return;
     const T fi = f ? f[i] : (T)0;
     T acc = row_dot<T, M>(rp[i], rp[i + 1], ci, v, e, 1, 0, i);
@@ -331,26 +229,13 @@ k_residual(int n, const int* __restrict__ rp, const int* __restrict__ ci, const 
 template <typename M>
 __global__ void __launch_bounds__(BAMG_BLK)
 k_spmv(int n, const int* __restrict__ rp, const int* __restrict__ ci, const M* __restrict__ v,
-       const double* __restrict__ x, double alpha, double* __restrict__ y) {
-    int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+       const double* __restrict__ x, double alpha, double* __restrict__ y, RowMask mk) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (!tile_active(mk, tile, BAMG_BLK, 1, n)) return;
+    int i = tile * BAMG_BLK + threadIdx.x;
     if (i >= n) return;
     double acc = row_dot<double, M>(rp[i], rp[i + 1], ci, v, x, 1, 0, i);
     y[i] = alpha * acc;
-}
-
-// f_c = Q r (restriction, ELL-9).
-template <typename T, typename M>
-__global__ void k_restrict(int nc, const int* __restrict__ qc, const M* __restrict__ qv,
-                           const T* __restrict__ r, T* __restrict__ fc) {
-    int I = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
-    if (I >= nc) return;
-    T acc = 0;
-#pragma unroll
-    for (int s = 0; s < 9; ++s) {
-        int i = qc[(size_t)I * 9 + s];
-        if (i >= 0) acc += (T)qv[(size_t)I * 9 + s] * r[i];
-    }
-    fc[I] = acc;
 }
 
 // f_c = Q r from the structure of Q alone: coarse row I takes the fine points
@@ -360,8 +245,10 @@ __global__ void k_restrict(int nc, const int* __restrict__ qc, const M* __restri
 template <typename T>
 __global__ void k_restrict_box(int nc, const ChainGeo* __restrict__ geoc, const ChainGeo* __restrict__ geof, int nch,
                                const unsigned short* __restrict__ qmask, const unsigned char* __restrict__ jcnt,
-                               const T* __restrict__ r, T* __restrict__ fc) {
-    int I = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+                               const T* __restrict__ r, T* __restrict__ fc, const int* __restrict__ act) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (!tile_active(RowMask{geoc, nch, act}, tile, BAMG_BLK, 1, nc)) return;
+    int I = tile * BAMG_BLK + threadIdx.x;
     if (I >= nc) return;
     const int ch = find_chain(geoc, nch, I);
     const ChainGeo gc = geoc[ch];
@@ -387,8 +274,10 @@ __global__ void k_restrict_box(int nc, const ChainGeo* __restrict__ geoc, const 
 // e += P e_c (prolongation, ELL-4).
 template <typename T, typename M>
 __global__ void k_prolong_add(int n, const int* __restrict__ pc, const M* __restrict__ pv,
-                              const T* __restrict__ ec, T* __restrict__ e) {
-    int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+                              const T* __restrict__ ec, T* __restrict__ e, RowMask mk) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (!tile_active(mk, tile, BAMG_BLK, 1, n)) return;
+    int i = tile * BAMG_BLK + threadIdx.x;
     if (i >= n) return;
     T acc = 0;
 #pragma unroll

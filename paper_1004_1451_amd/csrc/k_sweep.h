@@ -1,0 +1,139 @@
+// Relaxation sweeps on interleaved test vectors (Section 3, eq. amg_relax):
+// the row product used by every sweep and the vector forms of the multi-vector
+// sweep the autotuner chooses from.  Kept in a header of its own so that its
+// measured HBM traffic is tied to exactly this source.
+#pragma once
+#include "common.h"
+
+template <typename T, typename M>
+__device__ __forceinline__ T row_dot(int p0, int p1, const int* __restrict__ ci, const M* __restrict__ v,
+                                     const T* __restrict__ X, int R, int k, int self) {
+    T acc = 0;
+    for (int p = p0; p < p1; p += 4) {
+        int c[4];
+        M w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            bool ok = p + u < p1;
+            c[u] = ok ? ci[p + u] : self;
+            w[u] = ok ? v[p + u] : (M)0;
+        }
+        T x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = X[(size_t)c[u] * R + k];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += (T)w[u] * x[u];
+    }
+    return acc;
+}
+
+// Vector forms of the sweep for the autotuner: a thread owns VW adjacent
+// columns of one row (G = R / VW threads per row) and moves them with 8- or
+// 16-byte loads; blocks of BS threads.  Same arithmetic per entry as k_sweep
+// (products added in CSR order), so every variant gives the same bits.
+template <typename T, int VW>
+struct VecIO;
+template <> struct VecIO<double, 1> {
+    static __device__ __forceinline__ void ld(const double* p, double* x) { x[0] = *p; }
+    static __device__ __forceinline__ void st(double* p, const double* x) { *p = x[0]; }
+};
+template <> struct VecIO<double, 2> {
+    static __device__ __forceinline__ void ld(const double* p, double* x) {
+        const double2 v = *(const double2*)p; x[0] = v.x; x[1] = v.y;
+    }
+    static __device__ __forceinline__ void st(double* p, const double* x) { *(double2*)p = make_double2(x[0], x[1]); }
+};
+template <> struct VecIO<double, 4> {
+    static __device__ __forceinline__ void ld(const double* p, double* x) {
+        const double2 a = ((const double2*)p)[0], b = ((const double2*)p)[1];
+        x[0] = a.x; x[1] = a.y; x[2] = b.x; x[3] = b.y;
+    }
+    static __device__ __forceinline__ void st(double* p, const double* x) {
+        ((double2*)p)[0] = make_double2(x[0], x[1]);
+        ((double2*)p)[1] = make_double2(x[2], x[3]);
+    }
+};
+template <> struct VecIO<float, 1> {
+    static __device__ __forceinline__ void ld(const float* p, float* x) { x[0] = *p; }
+    static __device__ __forceinline__ void st(float* p, const float* x) { *p = x[0]; }
+};
+template <> struct VecIO<float, 2> {
+    static __device__ __forceinline__ void ld(const float* p, float* x) {
+        const float2 v = *(const float2*)p; x[0] = v.x; x[1] = v.y;
+    }
+    static __device__ __forceinline__ void st(float* p, const float* x) { *(float2*)p = make_float2(x[0], x[1]); }
+};
+template <> struct VecIO<float, 4> {
+    static __device__ __forceinline__ void ld(const float* p, float* x) {
+        const float4 v = *(const float4*)p; x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+    }
+    static __device__ __forceinline__ void st(float* p, const float* x) {
+        *(float4*)p = make_float4(x[0], x[1], x[2], x[3]);
+    }
+};
+
+// Wider groups: 3, 6 or 12 adjacent columns.  For doubles, VW even -> 16-byte
+// pieces (row bases are 16-byte aligned when R is even); otherwise 8-byte.
+// For floats, 4-float pieces when VW % 4 == 0, else 2-float or single.
+template <typename T, int VW>
+struct VecIOn {
+    static constexpr int P = sizeof(T) == 8 ? (VW % 2 == 0 ? 2 : 1) : (VW % 4 == 0 ? 4 : (VW % 2 == 0 ? 2 : 1));
+    static __device__ __forceinline__ void ld(const T* p, T* x) {
+#pragma unroll
+        for (int k = 0; k < VW; k += P) VecIO<T, P>::ld(p + k, x + k);
+    }
+    static __device__ __forceinline__ void st(T* p, const T* x) {
+#pragma unroll
+        for (int k = 0; k < VW; k += P) VecIO<T, P>::st(p + k, x + k);
+    }
+};
+template <> struct VecIO<double, 3> : VecIOn<double, 3> {};
+template <> struct VecIO<double, 6> : VecIOn<double, 6> {};
+template <> struct VecIO<double, 12> : VecIOn<double, 12> {};
+template <> struct VecIO<float, 3> : VecIOn<float, 3> {};
+template <> struct VecIO<float, 6> : VecIOn<float, 6> {};
+template <> struct VecIO<float, 12> : VecIOn<float, 12> {};
+
+template <typename T, typename M, int VW, int BS>
+__global__ void __launch_bounds__(BS)
+k_sweep_v(int n, int G, FastDiv divG, const int* __restrict__ rp, const int* __restrict__ ci,
+          const M* __restrict__ v, const M* __restrict__ dinv, const T* __restrict__ X,
+          const T* __restrict__ F, T* __restrict__ Y) {
+    const int t = xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
+    if (t >= n * G) return;
+    const int i = (int)divG.div((uint32_t)t), kg = t - i * G;
+    const int R = G * VW;
+    const size_t base = (size_t)i * R + (size_t)kg * VW;
+    T xt[VW], f[VW], acc[VW];
+    VecIO<T, VW>::ld(X + base, xt);
+    if (F) VecIO<T, VW>::ld(F + base, f);
+    else
+#pragma unroll
+        for (int q = 0; q < VW; ++q) f[q] = (T)0;
+#pragma unroll
+    for (int q = 0; q < VW; ++q) acc[q] = (T)0;
+    const T d = (T)dinv[i];
+    const int p0 = rp[i], p1 = rp[i + 1];
+    for (int p = p0; p < p1; p += 4) {
+        int c[4];
+        M w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool ok = p + u < p1;
+            c[u] = ok ? ci[p + u] : i;
+            w[u] = ok ? v[p + u] : (M)0;
+        }
+        T x[4][VW];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) VecIO<T, VW>::ld(X + (size_t)c[u] * R + (size_t)kg * VW, x[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < VW; ++q) acc[q] += (T)w[u] * x[u][q];
+    }
+    T y[VW];
+#pragma unroll
+    for (int q = 0; q < VW; ++q) y[q] = xt[q] + d * (f[q] - acc[q]);
+    VecIO<T, VW>::st(Y + base, y);
+}
+
