@@ -178,7 +178,7 @@ typedef struct {
                                order (least-squares form); needs collect      */
 
 /* Fill *opt with the defaults: levels 0, coarse_max 1024, nu_setup 4,
-   V(2,2), omega 0.7, caliber 4, n_eig 6, arnoldi_m 64, gmres_m 50,
+   V(2,2), omega 0.7, caliber 4, n_eig 6, arnoldi_m 40, gmres_m 50,
    FP64, LS interpolation, seed 0, no budget, no profiling, 2 setup passes,
    mlp_judge 2. */
 void bamg_options_default(bamg_options* opt);

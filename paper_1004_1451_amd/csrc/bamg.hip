@@ -815,8 +815,7 @@ struct Engine : bamg_ctx {
         const dim3 gv(nblk(maxnL), nch);
         hipLaunchKernelGGL(k_cz_densify<T>, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, Wp, bcolp);
         HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_cz_absmax_partial, dim3(64, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd,
-                           (const double*)Wp, part);
+        hipLaunchKernelGGL(k_cz_absmax_sparse<T>, dim3(64, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, part);
         LAUNCH(k_cz_absmax_final, nch, BAMG_BLK, s, 64, (const double*)part, scale);
         HIPCHK(hipGetLastError());
         {
@@ -833,12 +832,12 @@ struct Engine : bamg_ctx {
                                (const double*)Wp, Fp);
             HIPCHK(hipGetLastError());
             for (int k = 0; k + 1 < nxmax; ++k) {
-                LAUNCH(k_cz_diag, nch, BAMG_BLK, s, (const CoarseDesc*)cd, k, Fp, (const double*)scale, minpiv);
+                LAUNCH(k_cz_diag, nch, CZ_GJ_THREADS, s, (const CoarseDesc*)cd, k, Fp, (const double*)scale, minpiv);
                 hipLaunchKernelGGL(k_cz_elim, dim3(4, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, k, 0, Fp);
                 hipLaunchKernelGGL(k_cz_elim, dim3(4, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, k, 1, Fp);
                 HIPCHK(hipGetLastError());
             }
-            LAUNCH(k_cz_diag, nch, BAMG_BLK, s, (const CoarseDesc*)cd, -1, Fp, (const double*)scale, minpiv);
+            LAUNCH(k_cz_diag, nch, CZ_GJ_THREADS, s, (const CoarseDesc*)cd, -1, Fp, (const double*)scale, minpiv);
             hipLaunchKernelGGL(k_cz_subst, dim3(ceil_div(maxnL, 64), nch), dim3(BAMG_BLK), 0, s,
                                (const CoarseDesc*)cd, Wp, (const double*)Fp);
             HIPCHK(hipGetLastError());
@@ -1624,7 +1623,7 @@ void bamg_options_default(bamg_options* opt) {
     opt->omega = 0.7;
     opt->caliber = 4;
     opt->n_eig = 6;
-    opt->arnoldi_m = 64;
+    opt->arnoldi_m = 40;
     opt->gmres_m = 50;
     opt->precision = BAMG_FP64;
     opt->interp = BAMG_INTERP_LS;

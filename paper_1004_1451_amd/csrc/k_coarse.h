@@ -49,17 +49,19 @@ __global__ void k_cz_densify(const CoarseDesc* __restrict__ cd, double* __restri
     }
 }
 
-// max |B_L| per chain: block maxima over a grid-stride range (grid (P, nch))
-// into part[chain * P + block], then one block per chain -> scale[chain].
-__global__ void k_cz_absmax_partial(const CoarseDesc* __restrict__ cd, const double* __restrict__ Wp,
-                                    double* __restrict__ part) {
+// max |B_L| per chain (the pivot scale): block maxima over a grid-stride range
+// of the chain's nonzeros (grid (P, nch)) into part[chain * P + block], then
+// one block per chain -> scale[chain].  The nonzeros of the sparse B_L are
+// exactly those of its dense copy.
+template <typename M>
+__global__ void k_cz_absmax_sparse(const CoarseDesc* __restrict__ cd, double* __restrict__ part) {
     __shared__ double sh[BAMG_BLK];
     const CoarseDesc d = cd[blockIdx.y];
-    const double* W = Wp + d.woff;
+    const M* v = (const M*)d.bv;
+    const int p0 = d.brp[d.row0], p1 = d.brp[d.row0 + d.n];
     double m = 0;
-    const long long nn = (long long)d.n * d.n;
-    for (long long e = (long long)blockIdx.x * BAMG_BLK + threadIdx.x; e < nn; e += (long long)gridDim.x * BAMG_BLK)
-        m = fmax(m, fabs(W[e]));
+    for (int p = p0 + blockIdx.x * BAMG_BLK + threadIdx.x; p < p1; p += gridDim.x * BAMG_BLK)
+        m = fmax(m, fabs((double)v[p]));
     sh[threadIdx.x] = m;
     __syncthreads();
     for (int s = BAMG_BLK / 2; s > 0; s >>= 1) {
@@ -118,12 +120,15 @@ __global__ void k_cz_extract(const CoarseDesc* __restrict__ cd, const double* __
 // Invert diagonal block k of every chain with k < nx (k < 0: the chain's
 // last block).  One workgroup per chain: Gauss-Jordan elimination without
 // pivoting on the block padded to 64 x 64 with the identity.  Thread (w, c)
-// keeps column c of rows 16 w .. 16 w + 15 in registers; each step reads the
-// pivot column from the owning lanes (readlane) and the pivot row from LDS,
-// where its owner wave has put it, so the only LDS traffic per step is one
-// row.  Step st, for row r and column c (f = a_r,st, p = a_st,st):
+// of CZ_GJ_THREADS keeps column c of rows CZ_GJ_ROWS w .. + CZ_GJ_ROWS - 1 in
+// registers; each step reads the pivot column from the owning lanes
+// (readlane) and the pivot row from LDS, where its owner wave has put it, so
+// the only LDS traffic per step is one row.  Step st, for row r and column c
+// (f = a_r,st, p = a_st,st):
 //   a_st,c <- a_st,c / p,  a_r,st <- -f / p,  a_st,st <- 1 / p,
 //   a_r,c <- a_r,c - f a_st,c / p  (all other entries).
+#define CZ_GJ_THREADS 256
+#define CZ_GJ_ROWS (GJ_NB * BAMG_WAVE / CZ_GJ_THREADS)
 __device__ __forceinline__ double cz_readlane(double v, int lane) {
     int lo = __double2loint(v), hi = __double2hiint(v);
     lo = __builtin_amdgcn_readlane(lo, lane);
@@ -131,7 +136,7 @@ __device__ __forceinline__ double cz_readlane(double v, int lane) {
     return __hiloint2double(hi, lo);
 }
 
-__global__ void __launch_bounds__(BAMG_BLK)
+__global__ void __launch_bounds__(CZ_GJ_THREADS)
 k_cz_diag(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, const double* __restrict__ scale,
           double* __restrict__ minpiv) {
     const CoarseDesc d = cd[blockIdx.x];
@@ -141,18 +146,18 @@ k_cz_diag(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, con
     double* A = cz_blk(Fp, d, 0, kk);
     const int nb = d.ny;
     const int c = threadIdx.x % BAMG_WAVE, w = threadIdx.x / BAMG_WAVE;   // column, row block
-    double S[16];
+    double S[CZ_GJ_ROWS];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int r = 16 * w + i;
+    for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+        const int r = CZ_GJ_ROWS * w + i;
         S[i] = (r < nb && c < nb) ? A[r * nb + c] : (r == c ? 1.0 : 0.0);
     }
     const double sc = scale[blockIdx.x];
     double mp = 1e300;
-    for (int blk = 0; blk < 4; ++blk) {
+    for (int blk = 0; blk < GJ_NB / CZ_GJ_ROWS; ++blk) {
 #pragma unroll
-        for (int ii = 0; ii < 16; ++ii) {
-            const int st = 16 * blk + ii, buf = st & 1;
+        for (int ii = 0; ii < CZ_GJ_ROWS; ++ii) {
+            const int st = CZ_GJ_ROWS * blk + ii, buf = st & 1;
             if (w == blk) prow[buf][c] = S[ii];
             __syncthreads();
             const double piv = prow[buf][st];
@@ -161,9 +166,9 @@ k_cz_diag(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, con
             if (threadIdx.x == 0 && st < nb) mp = fmin(mp, fabs(piv) / sc);
             const bool ck = c == st;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
+            for (int i = 0; i < CZ_GJ_ROWS; ++i) {
                 const double f = cz_readlane(S[i], st);      // a_r,st from lane st
-                const bool rk = (16 * w + i) == st;
+                const bool rk = (CZ_GJ_ROWS * w + i) == st;
                 double v = S[i] - f * pr;
                 v = ck ? -f * ip : v;
                 v = rk ? pr : v;
@@ -173,8 +178,8 @@ k_cz_diag(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, con
         }
     }
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int r = 16 * w + i;
+    for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+        const int r = CZ_GJ_ROWS * w + i;
         if (r < nb && c < nb) A[r * nb + c] = S[i];
     }
     if (threadIdx.x == 0) minpiv[blockIdx.x] = fmin(minpiv[blockIdx.x], mp);
