@@ -343,10 +343,10 @@ struct Engine : bamg_ctx {
     T* sweep_tmp = nullptr;
     // FGMRES
     int m_alloc = 0;
-    double* hbuf2 = nullptr;
+    double *hbuf2 = nullptr, *gsaux = nullptr, *gscoef = nullptr;
     double *Vk = nullptr, *Zk = nullptr, *wk = nullptr, *Hg = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr,
            *ysol = nullptr, *hbuf = nullptr, *rvec = nullptr, *est = nullptr, *xperm = nullptr;
-    int *act = nullptr, *kd = nullptr, *act2 = nullptr;
+    int *act = nullptr, *kd = nullptr;
     int* cmask = nullptr;            // chains the cycle works on (nch > 1; all ones outside solve)
     double *vin = nullptr, *vout = nullptr;   // permuted vectors of bamg_apply_vcycle
     // graph of one cycle on fixed buffers
@@ -831,14 +831,19 @@ struct Engine : bamg_ctx {
             hipLaunchKernelGGL(k_cz_extract, dim3(nblk(bbmax), nxmax, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd,
                                (const double*)Wp, Fp);
             HIPCHK(hipGetLastError());
+            bool arrow = false;
+            for (auto& d : cdh) arrow |= d.periodic && d.nx >= 3;
+            const dim3 gl(arrow ? 4 : 1, nch);
             for (int k = 0; k + 1 < nxmax; ++k) {
-                LAUNCH(k_cz_diag, nch, CZ_GJ_THREADS, s, (const CoarseDesc*)cd, k, Fp, (const double*)scale, minpiv);
-                hipLaunchKernelGGL(k_cz_elim, dim3(4, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, k, 0, Fp);
-                hipLaunchKernelGGL(k_cz_elim, dim3(4, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, k, 1, Fp);
+                hipLaunchKernelGGL(k_cz_lu_step, gl, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, k, Fp,
+                                   (const double*)scale, minpiv);
+                if (arrow)
+                    hipLaunchKernelGGL(k_cz_elim_arrow, dim3(2, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, k, Fp);
                 HIPCHK(hipGetLastError());
             }
-            LAUNCH(k_cz_diag, nch, CZ_GJ_THREADS, s, (const CoarseDesc*)cd, -1, Fp, (const double*)scale, minpiv);
-            hipLaunchKernelGGL(k_cz_subst, dim3(ceil_div(maxnL, 64), nch), dim3(BAMG_BLK), 0, s,
+            hipLaunchKernelGGL(k_cz_lu_step, gl, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, -1, Fp,
+                               (const double*)scale, minpiv);
+            hipLaunchKernelGGL(k_cz_subst, dim3(ceil_div(maxnL, CZ_SUB_TC), nch), dim3(BAMG_BLK), 0, s,
                                (const CoarseDesc*)cd, Wp, (const double*)Fp);
             HIPCHK(hipGetLastError());
         }
@@ -1286,9 +1291,10 @@ struct Engine : bamg_ctx {
             ysol = A.alloc<double>((size_t)nch * GS);
             hbuf = A.alloc<double>((size_t)nch * GS);
             hbuf2 = A.alloc<double>((size_t)nch * GS);
+            gsaux = A.alloc<double>((size_t)nch * 3 * GS);
+            gscoef = A.alloc<double>((size_t)nch * GS_CS);
             est = A.alloc<double>(nch);
             act = cmask ? cmask : A.alloc<int>(nch);
-            act2 = A.alloc<int>(nch);
             kd = A.alloc<int>(nch);
             if (reordered) xperm = A.alloc<double>(N);
             m_alloc = m;
@@ -1359,35 +1365,23 @@ struct Engine : bamg_ctx {
                 ++inf.cycles;
                 LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)zj, 1.0, wk,
                        RowMask{g0, nch, cmask});
-                // classical Gram-Schmidt: first-pass dots (and ||w||^2), then
-                // the fused update + second-pass dots, then the second update
-                // where the first pass lost over half of ||w||^2, fused with
-                // the new norm
+                // Gram-Schmidt with the delayed second pass: dots of w, the
+                // per-chain step (finish v_j, correct column j-1, column j,
+                // Givens), and, for chains that go on, the update pass that
+                // finishes q_j and makes v_{j+1} with its dots
                 const int P0 = L[0].segp;
                 const dim3 gsg(P0, nch);
-                hipLaunchKernelGGL(k_seg_mdot_partial, gsg, dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, N, j + 1, j + 2,
-                                   (const int*)act, (const double*)Vk, (const double*)wk, part);
-                hipLaunchKernelGGL(k_seg_mdot_final, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0, j + 1,
-                                   j + 2, (const int*)act, (const double*)part, hbuf, GS, Hg + (size_t)j * ld, HSg);
+                auto pick = [&](auto k8, auto k16, auto k32, auto k64) {
+                    return j <= 8 ? k8 : j <= 16 ? k16 : j <= 32 ? k32 : k64;
+                };
+                hipLaunchKernelGGL(pick(k_gs_dots<8>, k_gs_dots<16>, k_gs_dots<32>, k_gs_dots<64>), gsg, dim3(BAMG_BLK),
+                                   0, s, g0, SEG_ROWS, N, j, (const int*)act, (const double*)Vk, (const double*)wk,
+                                   part, GS);
+                hipLaunchKernelGGL(k_gs_final, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0,
+                                   (const int*)act, (const double*)part, GS, hbuf, GS);
                 HIPCHK(hipGetLastError());
-                LAUNCH(k_seg_dgks, ceil_div(nch, 64), 64, s, nch, j + 1, act, (const double*)hbuf, GS, act2);
-                {
-                    auto kd_ = j + 1 <= 8 ? k_seg_upd_dots<8>
-                             : j + 1 <= 16 ? k_seg_upd_dots<16> : j + 1 <= 32 ? k_seg_upd_dots<32> : k_seg_upd_dots<64>;
-                    hipLaunchKernelGGL(kd_, gsg, dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, N, j + 1, (const int*)act,
-                                       (const double*)Vk, (const double*)hbuf, GS, wk, part);
-                }
-                hipLaunchKernelGGL(k_seg_mdot_final, dim3(j + 1, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0, j + 1,
-                                   j + 1, (const int*)act2, (const double*)part, hbuf2, GS, Hg + (size_t)j * ld, HSg);
-                hipLaunchKernelGGL(k_seg_upd_norm, gsg, dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, N, j + 1, (const int*)act,
-                                   (const int*)act2, (const double*)Vk, (const double*)hbuf2, GS, wk, part);
-                hipLaunchKernelGGL(k_seg_wave_final, dim3(nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0,
-                                   (const int*)act, (const double*)part, sc + 4, SCS);
-                HIPCHK(hipGetLastError());
-                LAUNCH(k_seg_scale, nb, BAMG_BLK, s, N, g0, nch, (const int*)act, (const double*)wk,
-                       (const double*)nullptr, (const double*)(sc + 4), SCS, 1, Vk + (size_t)(j + 1) * N);
-                LAUNCH(k_seg_givens, ceil_div(nch, 64), 64, s, nch, j, ld, (const int*)act, Hg, HSg,
-                       (const double*)(sc + 4), SCS, cs, sn, g, GS, est);
+                LAUNCH(k_gs_step, ceil_div(nch, 64), 64, s, nch, j, ld, (const int*)act, (const double*)hbuf2,
+                       (const double*)hbuf, GS, Hg, HSg, cs, sn, g, gsaux, GS, gscoef, est);
                 // |g_{j+1}| = 0 also covers a breakdown (||w|| = 0 gives s_j = 0)
                 std::vector<double> e = getn(est, nch);
                 bool any = false;
@@ -1397,8 +1391,14 @@ struct Engine : bamg_ctx {
                     if (e[c] <= itol[c] || e[c] == 0.0) hact[c] = 0;
                     any |= (bool)hact[c];
                 }
+                if (!any || j + 1 >= m || inf.cycles >= max_cycles) break;
                 HIPCHK(hipMemcpyAsync(act, hact.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
-                if (!any) break;
+                hipLaunchKernelGGL(pick(k_gs_update<8>, k_gs_update<16>, k_gs_update<32>, k_gs_update<64>), gsg,
+                                   dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, N, j, (const int*)act, Vk, (const double*)wk,
+                                   (const double*)gscoef, part, GS);
+                hipLaunchKernelGGL(k_gs_final, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0,
+                                   (const int*)act, (const double*)part, GS, hbuf2, GS);
+                HIPCHK(hipGetLastError());
             }
             HIPCHK(hipMemcpyAsync(kd, hkd.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
             LAUNCH(k_seg_gmres_y, ceil_div(nch, 64), 64, s, nch, ld, (const int*)kd, (const double*)Hg, HSg,

@@ -56,6 +56,34 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;   // valid in lane 0
 }
 
+// Sums of K per-lane values a[0..K-1] over the wavefront at once (K = 8, 16,
+// 32 or 64): on each of the top log2 K lane bits every lane keeps one half of
+// its values and adds the partner lane's copy of that half (K - 1 exchanges
+// in all, instead of 6 K for K separate sums), then the lanes that share an
+// index add up over the remaining bits.  On return a[0] of lane l is the
+// total of value l >> (6 - log2 K); the order of the additions is fixed.
+template <int K, int H, int O>
+__device__ __forceinline__ void wave_sum_halve(double (&a)[K], int lane) {
+    if constexpr (H >= 1) {
+        const bool up = (lane & O) != 0;
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const double keep = up ? a[i + H] : a[i];
+            const double send = up ? a[i] : a[i + H];
+            a[i] = keep + __shfl_xor(send, O, BAMG_WAVE);
+        }
+        wave_sum_halve<K, H / 2, O / 2>(a, lane);
+    } else {
+#pragma unroll
+        for (int o = O; o >= 1; o >>= 1) a[0] += __shfl_xor(a[0], o, BAMG_WAVE);
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void wave_sum_many(double (&a)[K]) {
+    wave_sum_halve<K, K / 2, BAMG_WAVE / 2>(a, threadIdx.x % BAMG_WAVE);
+}
+
 // Sum over a block of BAMG_BLK threads in a fixed order (lane tree, then the
 // four wave totals in order).  Result valid in thread 0.
 template <typename T>

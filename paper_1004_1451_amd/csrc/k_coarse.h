@@ -117,87 +117,69 @@ __global__ void k_cz_extract(const CoarseDesc* __restrict__ cd, const double* __
     }
 }
 
-// Invert diagonal block k of every chain with k < nx (k < 0: the chain's
-// last block).  One workgroup per chain: Gauss-Jordan elimination without
+// Inversion of one diagonal block: Gauss-Jordan elimination without
 // pivoting on the block padded to 64 x 64 with the identity.  Thread (w, c)
 // of CZ_GJ_THREADS keeps column c of rows CZ_GJ_ROWS w .. + CZ_GJ_ROWS - 1 in
-// registers; each step reads the pivot column from the owning lanes
-// (readlane) and the pivot row from LDS, where its owner wave has put it, so
-// the only LDS traffic per step is one row.  Step st, for row r and column c
-// (f = a_r,st, p = a_st,st):
+// registers.  Step st, for row r and column c (f = a_r,st, p = a_st,st):
 //   a_st,c <- a_st,c / p,  a_r,st <- -f / p,  a_st,st <- 1 / p,
 //   a_r,c <- a_r,c - f a_st,c / p  (all other entries).
+// Before the step's barrier the owner wave puts the pivot row and lane st of
+// every wave its part of the pivot column into LDS (two buffers, alternating),
+// so each thread then does one fused multiply-add per entry: the pivot column
+// takes a_r,st - f (1 + 1/p) = -f / p, and the owner rewrites the pivot row
+// afterwards.  1/p is v_rcp_f64 refined by two Newton steps.
 #define CZ_GJ_THREADS 256
 #define CZ_GJ_ROWS (GJ_NB * BAMG_WAVE / CZ_GJ_THREADS)
-__device__ __forceinline__ double cz_readlane(double v, int lane) {
-    int lo = __double2loint(v), hi = __double2hiint(v);
-    lo = __builtin_amdgcn_readlane(lo, lane);
-    hi = __builtin_amdgcn_readlane(hi, lane);
-    return __hiloint2double(hi, lo);
+__device__ __forceinline__ double cz_recip(double p) {
+    double r = __builtin_amdgcn_rcp(p);
+    double e = fma(-p, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-p, r, 1.0);
+    return fma(r, e, r);
 }
 
-__global__ void __launch_bounds__(CZ_GJ_THREADS)
-k_cz_diag(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, const double* __restrict__ scale,
-          double* __restrict__ minpiv) {
-    const CoarseDesc d = cd[blockIdx.x];
-    const int kk = k < 0 ? d.nx - 1 : k;
-    if (kk >= d.nx - (k < 0 ? 0 : 1) || d.n < 2) return;
-    __shared__ double prow[2][GJ_NB];
-    double* A = cz_blk(Fp, d, 0, kk);
-    const int nb = d.ny;
-    const int c = threadIdx.x % BAMG_WAVE, w = threadIdx.x / BAMG_WAVE;   // column, row block
-    double S[CZ_GJ_ROWS];
-#pragma unroll
-    for (int i = 0; i < CZ_GJ_ROWS; ++i) {
-        const int r = CZ_GJ_ROWS * w + i;
-        S[i] = (r < nb && c < nb) ? A[r * nb + c] : (r == c ? 1.0 : 0.0);
-    }
-    const double sc = scale[blockIdx.x];
-    double mp = 1e300;
+// Gauss-Jordan on the 64 x 64 block held in S by the CZ_GJ_THREADS threads
+// (w = wave, c = lane); mp takes the smallest |pivot| / sc of the first nb.
+__device__ __forceinline__ void cz_gj(double (&S)[CZ_GJ_ROWS], int w, int c, int nb, double sc, double& mp,
+                                      double (*prow)[GJ_NB], double (*pcol)[GJ_NB]) {
     for (int blk = 0; blk < GJ_NB / CZ_GJ_ROWS; ++blk) {
 #pragma unroll
         for (int ii = 0; ii < CZ_GJ_ROWS; ++ii) {
             const int st = CZ_GJ_ROWS * blk + ii, buf = st & 1;
+            const bool ck = c == st;
             if (w == blk) prow[buf][c] = S[ii];
+            if (ck)
+#pragma unroll
+                for (int i = 0; i < CZ_GJ_ROWS; ++i) pcol[buf][CZ_GJ_ROWS * w + i] = S[i];
             __syncthreads();
             const double piv = prow[buf][st];
-            const double ip = 1.0 / piv;
+            const double ip = cz_recip(piv);
             const double pr = prow[buf][c] * ip;
+            const double pm = ck ? 1.0 + ip : pr;
             if (threadIdx.x == 0 && st < nb) mp = fmin(mp, fabs(piv) / sc);
-            const bool ck = c == st;
 #pragma unroll
-            for (int i = 0; i < CZ_GJ_ROWS; ++i) {
-                const double f = cz_readlane(S[i], st);      // a_r,st from lane st
-                const bool rk = (CZ_GJ_ROWS * w + i) == st;
-                double v = S[i] - f * pr;
-                v = ck ? -f * ip : v;
-                v = rk ? pr : v;
-                v = (rk && ck) ? ip : v;
-                S[i] = v;
-            }
+            for (int i = 0; i < CZ_GJ_ROWS; ++i) S[i] = fma(-pcol[buf][CZ_GJ_ROWS * w + i], pm, S[i]);
+            if (w == blk) S[ii] = ck ? ip : pr;
         }
     }
-#pragma unroll
-    for (int i = 0; i < CZ_GJ_ROWS; ++i) {
-        const int r = CZ_GJ_ROWS * w + i;
-        if (r < nb && c < nb) A[r * nb + c] = S[i];
-    }
-    if (threadIdx.x == 0) minpiv[blockIdx.x] = fmin(minpiv[blockIdx.x], mp);
 }
 
-// One b x b product C = A B (mode 0, C may alias A) or C -= A B (mode 1).
-__device__ void cz_gemm(int b, const double* A, const double* Bm, double* C, int mode, double (*AsT)[GJ_NB + 2],
-                        double (*Bs)[GJ_NB + 2]) {
-    const int tid = threadIdx.x;
-    for (int e = tid; e < GJ_NB * GJ_NB; e += BAMG_BLK) {
-        int r = e / GJ_NB, c = e % GJ_NB;
-        bool ok = r < b && c < b;
+// One b x b product C = A B (mode 0, C may alias A) or C -= A B (mode 1):
+// A staged transposed and B as is in LDS (zero-padded to 64 x 64), each
+// thread a 4 x 4 tile of C at rows tr.., columns tc.., summed over t in
+// ascending order.
+__device__ __forceinline__ void cz_stage(int b, const double* A, double (*AsT)[GJ_NB + 2], const double* Bm,
+                                         double (*Bs)[GJ_NB + 2]) {
+    for (int e = threadIdx.x; e < GJ_NB * GJ_NB; e += BAMG_BLK) {
+        const int r = e / GJ_NB, c = e % GJ_NB;
+        const bool ok = r < b && c < b;
         AsT[c][r] = ok ? A[r * b + c] : 0.0;
-        Bs[r][c] = ok ? Bm[r * b + c] : 0.0;
+        if (Bm) Bs[r][c] = ok ? Bm[r * b + c] : 0.0;
     }
-    __syncthreads();
-    const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
-    double acc[4][4];
+}
+
+__device__ __forceinline__ void cz_tile(int b, const double (*AsT)[GJ_NB + 2], const double (*Bs)[GJ_NB + 2], int tr,
+                                        int tc, double (&acc)[4][4]) {
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -213,6 +195,15 @@ __device__ void cz_gemm(int b, const double* A, const double* Bm, double* C, int
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc[a][c] += av[a] * bv[c];
     }
+}
+
+__device__ void cz_gemm(int b, const double* A, const double* Bm, double* C, int mode, double (*AsT)[GJ_NB + 2],
+                        double (*Bs)[GJ_NB + 2]) {
+    cz_stage(b, A, AsT, Bm, Bs);
+    __syncthreads();
+    const int tid = threadIdx.x, tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+    double acc[4][4];
+    cz_tile(b, AsT, Bs, tr, tc, acc);
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -228,13 +219,10 @@ __device__ void cz_gemm(int b, const double* A, const double* Bm, double* C, int
 // Elimination of block column k for every chain with k < K = nx - 1.
 // phase 0: multipliers  Lo[k+1] = Lo[k+1] Dinv_k  (and Rw[k] = Rw[k] Dinv_k);
 // phase 1: updates of the blocks in rows {k+1, K} x columns {k+1, K}.
-// blockIdx.x = product (0..3), blockIdx.y = chain.
-__global__ void __launch_bounds__(BAMG_BLK)
-k_cz_elim(const CoarseDesc* __restrict__ cd, int k, int phase, double* __restrict__ Fp) {
-    __shared__ double AsT[GJ_NB][GJ_NB + 2];
-    __shared__ double Bs[GJ_NB][GJ_NB + 2];
-    const CoarseDesc d = cd[blockIdx.y];
-    const int K = d.nx - 1, q = blockIdx.x;
+// q = product (0..3); one workgroup.
+__device__ void cz_elim_part(const CoarseDesc& d, int k, int phase, int q, double* __restrict__ Fp,
+                             double (*AsT)[GJ_NB + 2], double (*Bs)[GJ_NB + 2]) {
+    const int K = d.nx - 1;
     if (k >= K || d.n < 2) return;
     const bool arrow = d.periodic && d.nx >= 3;
     const int b = d.ny;
@@ -265,10 +253,108 @@ k_cz_elim(const CoarseDesc* __restrict__ cd, int k, int phase, double* __restric
     cz_gemm(b, A, Bm, C, mode, AsT, Bs);
 }
 
-// All substitution steps of W = (L U)^-1 for one 64-column tile of one chain
-// per workgroup (grid (ceil(n / 64), nch)): the columns of W are independent
-// right-hand sides (the identity), so a workgroup walks every block row on
-// its own, with the previous block row of the solution kept in LDS.
+// Multipliers of step k for the periodic (arrow) chains only (grid (2, nch)):
+// Lo_{k+1} = Lo_{k+1} Dinv_k and Rw_k = Rw_k Dinv_k.  The other chains get
+// theirs inside k_cz_lu_step.
+__global__ void __launch_bounds__(BAMG_BLK)
+k_cz_elim_arrow(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp) {
+    __shared__ double AsT[GJ_NB][GJ_NB + 2];
+    __shared__ double Bs[GJ_NB][GJ_NB + 2];
+    const CoarseDesc d = cd[blockIdx.y];
+    if (!(d.periodic && d.nx >= 3)) return;
+    cz_elim_part(d, k, 0, blockIdx.x, Fp, AsT, Bs);
+}
+
+// Step k of the block LU for every chain (k < 0: the chain's last block K),
+// grid (1 or 4, nch).  Workgroup 0 forms D_k - Lo_k Up_{k-1} (the update of
+// step k-1, summed as cz_gemm does) in the Gauss-Jordan registers, inverts
+// it, stores Dinv_k and, for chains without the periodic arrow, the
+// multipliers Lo_{k+1} = Lo_{k+1} Dinv_k from the same registers.  For the
+// periodic chains, workgroups 1..3 do the other updates of step k-1, which
+// touch none of the blocks workgroup 0 reads or writes, and their
+// multipliers follow in k_cz_elim_arrow.  One launch per block row instead
+// of three.
+__global__ void __launch_bounds__(BAMG_BLK)
+k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, const double* __restrict__ scale,
+             double* __restrict__ minpiv) {
+    static_assert(CZ_GJ_THREADS == BAMG_BLK, "one workgroup size for both parts");
+    __shared__ double lds[2 * GJ_NB * (GJ_NB + 2)];
+    __shared__ double prow[2][GJ_NB];
+    __shared__ __align__(16) double pcol[2][GJ_NB];
+    const CoarseDesc d = cd[blockIdx.y];
+    const int K = d.nx - 1, q = blockIdx.x;
+    const int kk = k < 0 ? K : k;
+    if (d.n < 2 || (k >= 0 && k >= K)) return;
+    const bool arrow = d.periodic && d.nx >= 3;
+    if (q > 0) {
+        if (arrow && kk >= 1)
+            cz_elim_part(d, kk - 1, 1, q, Fp, (double(*)[GJ_NB + 2])lds, (double(*)[GJ_NB + 2])(lds + GJ_NB * (GJ_NB + 2)));
+        return;
+    }
+    double (*AsT)[GJ_NB + 2] = (double(*)[GJ_NB + 2])lds;
+    double (*Bs)[GJ_NB + 2] = (double(*)[GJ_NB + 2])(lds + GJ_NB * (GJ_NB + 2));
+    const int b = d.ny, tid = threadIdx.x;
+    const int c = tid % BAMG_WAVE, w = tid / BAMG_WAVE;
+    const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+    double* D = cz_blk(Fp, d, 0, kk);
+    double S[CZ_GJ_ROWS];
+    if (kk >= 1) {
+        // Lo_k Up_{k-1} in 4 x 4 tiles, then through LDS into this
+        // thread's column strip
+        cz_stage(b, cz_blk(Fp, d, 2, kk), AsT, cz_blk(Fp, d, 1, kk - 1), Bs);
+        __syncthreads();
+        double acc[4][4];
+        cz_tile(b, AsT, Bs, tr, tc, acc);
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) AsT[tr + a][tc + q4] = acc[a][q4];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+            const int r = CZ_GJ_ROWS * w + i;
+            S[i] = (r < b && c < b) ? D[r * b + c] - AsT[r][c] : (r == c ? 1.0 : 0.0);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+            const int r = CZ_GJ_ROWS * w + i;
+            S[i] = (r < b && c < b) ? D[r * b + c] : (r == c ? 1.0 : 0.0);
+        }
+    }
+    double mp = 1e300;
+    cz_gj(S, w, c, b, scale[blockIdx.y], mp, prow, pcol);
+#pragma unroll
+    for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+        const int r = CZ_GJ_ROWS * w + i;
+        if (r < b && c < b) D[r * b + c] = S[i];
+    }
+    if (tid == 0) minpiv[blockIdx.y] = fmin(minpiv[blockIdx.y], mp);
+    if (!arrow && kk < K) {
+        double* Lo1 = cz_blk(Fp, d, 2, kk + 1);
+        __syncthreads();
+        cz_stage(b, Lo1, AsT, nullptr, Bs);
+#pragma unroll
+        for (int i = 0; i < CZ_GJ_ROWS; ++i) Bs[CZ_GJ_ROWS * w + i][c] = S[i];
+        __syncthreads();
+        double acc[4][4];
+        cz_tile(b, AsT, Bs, tr, tc, acc);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const int r = tr + a, cc = tc + q4;
+                if (r < b && cc < b) Lo1[r * b + cc] = acc[a][q4];
+            }
+    }
+}
+
+// All substitution steps of W = (L U)^-1 for one tile of CZ_SUB_TC columns
+// of one chain per workgroup (grid (ceil(n / CZ_SUB_TC), nch)): the columns of
+// W are independent right-hand sides (the identity), so a workgroup walks
+// every block row on its own, with the previous block row of the solution
+// kept in LDS.
 //   forward:  Y_0 = I_0;  Y_s = I_s - Lo_s Y_{s-1}  (s < K);
 //             Y_K = I_K - sum_{j < K-1} Rw_j Y_j - Lo_K Y_{K-1}  (arrow terms
 //             when periodic), in that order;
@@ -276,52 +362,40 @@ k_cz_elim(const CoarseDesc* __restrict__ cd, int k, int phase, double* __restric
 //             X_k = Dinv_k (Y_k - Up_k X_{k+1} - Cl_k X_K)  (k = K-1 .. 0).
 // Lo_s and Rw_j hold the multipliers (already times Dinv), Dk the inverted
 // diagonal blocks of the LU; every product adds over t in ascending order.
-__device__ __forceinline__ void cz_ident(int blk, int b, int c0, int w, int tr, int tc, double X[4][4]) {
+// Block rows above the tile's first identity block s0 have Y_s = 0: they are
+// stored as zeros and take no products.  Thread t keeps rows 4 (t / 16) ..
+// + 3 of column t % 16 of the tile.
+#define CZ_SUB_TC 16
+__device__ __forceinline__ void cz_ident(int blk, int b, int c0, int w, int tr, int tc, double X[4]) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int r = tr + a, c = tc + q;
-            X[a][q] = (r < b && c < w && blk * b + r == c0 + c) ? 1.0 : 0.0;
-        }
+    for (int a = 0; a < 4; ++a) {
+        const int r = tr + a;
+        X[a] = (r < b && tc < w && blk * b + r == c0 + tc) ? 1.0 : 0.0;
+    }
 }
 
-// acc (+)= Ms[rows tr.., 0:b] * Xs[0:b, cols tc..]
-__device__ __forceinline__ void cz_mac(int b, const double (*Ms)[GJ_NB + 1], const double (*Xs)[GJ_NB + 1], int tr,
-                                       int tc, double acc[4][4], double sign) {
+// acc (+)= sign Ms[rows tr.., 0:b] * Xs[0:b, column tc]
+__device__ __forceinline__ void cz_mac(int b, const double (*Ms)[GJ_NB + 1], const double (*Xs)[CZ_SUB_TC + 1],
+                                       int tr, int tc, double acc[4], double sign) {
     for (int t = 0; t < b; ++t) {
-        double mv[4], xv[4];
+        const double xv = sign * Xs[t][tc];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) mv[a] = sign * Ms[tr + a][t];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) xv[q] = Xs[t][tc + q];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[a][q] += mv[a] * xv[q];
+        for (int a = 0; a < 4; ++a) acc[a] += Ms[tr + a][t] * xv;
     }
 }
 
-__device__ __forceinline__ void cz_load_blk(int b, const double* __restrict__ M, double (*Ms)[GJ_NB + 1]) {
-    for (int e = threadIdx.x; e < GJ_NB * GJ_NB; e += BAMG_BLK) {
-        const int r = e / GJ_NB, c = e % GJ_NB;
-        Ms[r][c] = (r < b && c < b) ? M[r * b + c] : 0.0;
-    }
-}
-
-__device__ __forceinline__ void cz_put(const double X[4][4], double (*Xs)[GJ_NB + 1], int tr, int tc) {
+__device__ __forceinline__ void cz_put(const double X[4], double (*Xs)[CZ_SUB_TC + 1], int tr, int tc) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Xs[tr + a][tc + q] = X[a][q];
+    for (int a = 0; a < 4; ++a) Xs[tr + a][tc] = X[a];
 }
 
 // The blocks a substitution workgroup multiplies by, in the order it uses
-// them (index part * nx + k into the chain's block storage).
-__device__ int cz_subst_sequence(int K, bool arrow, int* seq) {
+// them (index part * nx + k into the chain's block storage), for a tile whose
+// first identity block is s0.
+__device__ int cz_subst_sequence(int K, bool arrow, int s0, int* seq) {
     int m = 0;
-    for (int s = 0; s < K; ++s) {
-        if (s >= 1) seq[m++] = 2 * (K + 1) + s;               // Lo_s
+    for (int s = s0; s < K; ++s) {
+        if (s > s0) seq[m++] = 2 * (K + 1) + s;               // Lo_s
         if (arrow && s < K - 1) seq[m++] = 4 * (K + 1) + s;   // Rw_s
         if (s == K - 1) seq[m++] = 2 * (K + 1) + K;           // Lo_K
     }
@@ -337,21 +411,22 @@ __device__ int cz_subst_sequence(int K, bool arrow, int* seq) {
 __global__ void __launch_bounds__(BAMG_BLK)
 k_cz_subst(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const double* __restrict__ Fp) {
     __shared__ double Ms[GJ_NB][GJ_NB + 1];
-    __shared__ double Xs[GJ_NB][GJ_NB + 1];
-    __shared__ double Ks[GJ_NB][GJ_NB + 1];
+    __shared__ double Xs[GJ_NB][CZ_SUB_TC + 1];
+    __shared__ double Ks[GJ_NB][CZ_SUB_TC + 1];
     __shared__ int seq[5 * CZ_MAX_NX + 8];
     __shared__ int nseq;
     const CoarseDesc d = cd[blockIdx.y];
     const int K = d.nx - 1, b = d.ny, n = d.n;
-    const int c0 = blockIdx.x * 64;
+    const int c0 = blockIdx.x * CZ_SUB_TC;
     if (n < 2 || c0 >= n) return;
     const bool arrow = d.periodic && d.nx >= 3;
     const double* F = Fp + d.boff;
     double* W = Wp + d.woff;
-    const int w = min(64, n - c0);
-    const int tid = threadIdx.x, tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+    const int w = min(CZ_SUB_TC, n - c0);
+    const int s0 = c0 / b;
+    const int tid = threadIdx.x, tr = (tid / CZ_SUB_TC) * 4, tc = tid % CZ_SUB_TC;
     const long long bb = (long long)b * b;
-    if (tid == 0) nseq = cz_subst_sequence(K, arrow, seq);
+    if (tid == 0) nseq = cz_subst_sequence(K, arrow, s0, seq);
     __syncthreads();
     // The next block of the sequence is loaded into registers while the
     // current one is in use; next_block() moves it to Ms (the caller has
@@ -375,21 +450,22 @@ k_cz_subst(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const dou
         if (++sidx < nseq) fetch(sidx);
     };
     fetch(0);
-    auto store = [&](int blk, const double X[4][4]) {
+    auto store = [&](int blk, const double X[4]) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int r = tr + a, c = tc + q;
-                if (r < b && c < w) W[(size_t)(blk * b + r) * n + c0 + c] = X[a][q];
-            }
+        for (int a = 0; a < 4; ++a) {
+            const int r = tr + a;
+            if (r < b && tc < w) W[(size_t)(blk * b + r) * n + c0 + tc] = X[a];
+        }
     };
-    double T[4][4], TK[4][4];
+    double T[4], TK[4];
     cz_ident(K, b, c0, w, tr, tc, TK);
     // forward substitution (L has unit diagonal blocks)
-    for (int s = 0; s < K; ++s) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) T[a] = 0.0;
+    for (int s = 0; s < min(s0, K); ++s) store(s, T);
+    for (int s = s0; s < K; ++s) {
         cz_ident(s, b, c0, w, tr, tc, T);
-        if (s >= 1) {                                // Xs holds Y_{s-1}
+        if (s > s0) {                                // Xs holds Y_{s-1}
             __syncthreads();
             next_block();                            // Lo_s
             __syncthreads();
@@ -416,9 +492,7 @@ k_cz_subst(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const dou
     cz_put(TK, Xs, tr, tc);
     __syncthreads();
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) T[a][q] = 0.0;
+    for (int a = 0; a < 4; ++a) T[a] = 0.0;
     cz_mac(b, Ms, Xs, tr, tc, T, 1.0);
     store(K, T);
     __syncthreads();
@@ -426,14 +500,12 @@ k_cz_subst(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const dou
     cz_put(T, Xs, tr, tc);                           // X_{k+1} for k = K-1
     // backward substitution
     for (int k = K - 1; k >= 0; --k) {
-        double U[4][4];
+        double U[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int r = tr + a, c = tc + q;
-                U[a][q] = (r < b && c < w) ? W[(size_t)(k * b + r) * n + c0 + c] : 0.0;
-            }
+        for (int a = 0; a < 4; ++a) {
+            const int r = tr + a;
+            U[a] = (r < b && tc < w) ? W[(size_t)(k * b + r) * n + c0 + tc] : 0.0;
+        }
         __syncthreads();
         next_block();                                // Up_k
         __syncthreads();
@@ -449,9 +521,7 @@ k_cz_subst(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const dou
         cz_put(U, Xs, tr, tc);
         __syncthreads();
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) T[a][q] = 0.0;
+        for (int a = 0; a < 4; ++a) T[a] = 0.0;
         cz_mac(b, Ms, Xs, tr, tc, T, 1.0);
         store(k, T);
         __syncthreads();

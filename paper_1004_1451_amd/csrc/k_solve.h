@@ -256,175 +256,137 @@ __global__ void k_seg_reduce_final(const ChainGeo* __restrict__ geo, int seg_row
     if (threadIdx.x == 0) out[(size_t)blockIdx.x * stride] = s;
 }
 
-// Multi-dots per chain: part[c][chunk*4 + wave][nv] (wave partials, no
-// block barrier); only chains with act[c] != 0.  Chunk = seg_rows rows.
-// Dots b < nb are <V_b, w>; with nv = nb + 1 the last one is <w, w>.
-__global__ void __launch_bounds__(BAMG_BLK)
-k_seg_mdot_partial(const ChainGeo* __restrict__ geo, int seg_rows, int N, int nb, int nv, const int* __restrict__ act,
-                   const double* __restrict__ V, const double* __restrict__ w, double* __restrict__ part) {
-    const ChainGeo g = geo[blockIdx.y];
-    if (!act[blockIdx.y]) return;
-    const int lane = threadIdx.x % BAMG_WAVE, wv = threadIdx.x / BAMG_WAVE;
-    const int i0 = g.off + blockIdx.x * seg_rows, i1 = min(g.off + g.n, i0 + seg_rows);
-    if (i0 >= i1) return;
-    const size_t slot = (((size_t)blockIdx.y * gridDim.x + blockIdx.x) * (BAMG_BLK / BAMG_WAVE) + wv) * nv;
-    // eight dots per pass over the chunk: w is read once per eight vectors
-    for (int b0 = 0; b0 < nv; b0 += 8) {
-        double s[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) s[q] = 0;
-        for (int i = i0 + threadIdx.x; i < i1; i += BAMG_BLK) {
-            const double wi = w[i];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int b = b0 + q;
-                if (b < nv) s[q] += (b < nb ? V[(size_t)b * N + i] : wi) * wi;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const double t = wave_sum(s[q]);
-            if (lane == 0 && b0 + q < nv) part[slot + b0 + q] = t;
-        }
-    }
-}
-
-// h[c*HS + b] = sum of chain c's wave partials (its own chunk count, stride
-// P chunks); hacc[c*HAS + b] += h for the basis dots b < nb.  Block (b, c).
-__global__ void k_seg_mdot_final(const ChainGeo* __restrict__ geo, int seg_rows, int P, int nb, int nv,
-                                 const int* __restrict__ act, const double* __restrict__ part, double* __restrict__ h,
-                                 int HS, double* __restrict__ hacc, int HAS) {
-    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
-    const int b = blockIdx.x, c = blockIdx.y;
-    if (!act[c]) return;
-    const int WPB = BAMG_BLK / BAMG_WAVE;
-    const int np = ((geo[c].n + seg_rows - 1) / seg_rows) * WPB;
-    double s = 0;
-    for (int j = threadIdx.x; j < np; j += BAMG_BLK) s += part[((size_t)c * P * WPB + j) * nv + b];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) {
-        h[(size_t)c * HS + b] = s;
-        if (b < nb) hacc[(size_t)c * HAS + b] += s;
-    }
-}
-
-// Second Gram-Schmidt pass only where the first lost more than half of
-// ||w||^2 (the test of Daniel, Gragg, Kaufman and Stewart with eta^2 = 1/2):
-// after w' = w - V h, ||w'||^2 = ||w||^2 - ||h||^2 for orthonormal V.
-// act2[c] = act[c] && ||w||^2 - ||h||^2 < ||w||^2 / 2  (h[c*HS + nb] = ||w||^2).
-__global__ void k_seg_dgks(int nch, int nb, const int* __restrict__ act, const double* __restrict__ h, int HS,
-                           int* __restrict__ act2) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nch) return;
-    int need = 0;
-    if (act[c]) {
-        const double* hc = h + (size_t)c * HS;
-        double hh = 0;
-        for (int b = 0; b < nb; ++b) hh += hc[b] * hc[b];
-        const double ww = hc[nb];
-        need = (ww - hh) < 0.5 * ww;
-    }
-    act2[c] = need;
-}
-
-// Fused Gram-Schmidt passes over a row chunk of each chain (chunk and wave
-// partials in the layout of k_seg_mdot_partial).
-// k_seg_upd_dots: w <- w - sum_{b<nb} h_b V_b on chains with act, then the
-// dots <V_b, w> of the updated w (the second pass's coefficients): each row's
-// V values are loaded once into registers and serve the update and the dots.
-// MAXB (>= nb) values and accumulators per thread, in registers.
+// ---------------------------------------------------------------------------
+// Arnoldi orthogonalisation of the flexible GMRES: classical Gram-Schmidt with
+// one reorthogonalisation, the second pass delayed into the next step so that
+// every Arnoldi step reads the basis twice (one pass of dots, one of updates).
+// At step j the basis holds q_0 .. q_{j-1} (finished) and v_j (one pass of
+// Gram-Schmidt, norm only estimated).  The dots pass takes w = B z_j; the
+// update pass finishes q_j = (v_j - sum a_b q_b) / alpha and writes the next
+// provisional vector v_{j+1} = (w - sum d_b q_b - h q_j) / nu, whose dots with
+// q_0 .. q_j and itself it also returns.  In flexible GMRES z_j may be any
+// vector, so preconditioning v_j before it is finished only changes the search
+// direction, and the Arnoldi relation B z_{j-1} = Q h + nu v_j becomes exact
+// once column j-1 is corrected with v_j = Q a + alpha q_j.
+//
+// Both passes return, for nb finished vectors, nb + 2 dots per chain:
+//   d < nb: <q_d, x>,  d = nb: <y, x>,  d = nb + 1: <x, x>
+// (dots pass: x = w, y = v_nb; update pass: x = v_{nb+1}, y = q_nb), as one
+// value per chunk of seg_rows rows in part[((c NDM) + d) P + chunk].
 #define GS_MAXB 64
-template <int MAXB>
-__global__ void __launch_bounds__(BAMG_BLK)
-k_seg_upd_dots(const ChainGeo* __restrict__ geo, int seg_rows, int N, int nb, const int* __restrict__ act,
-               const double* __restrict__ V, const double* __restrict__ h, int HS, double* __restrict__ w,
-               double* __restrict__ part) {
-    const ChainGeo g = geo[blockIdx.y];
-    if (!act[blockIdx.y]) return;
+#define GS_CS (2 * GS_MAXB + 4)
+
+template <int K>
+__device__ __forceinline__ void gs_store_partials(double (&acc)[K], double ey, double ex, int nb,
+                                                  double* __restrict__ part, int NDM, double* red) {
+    constexpr int SH = K >= 64 ? 0 : K >= 32 ? 1 : K >= 16 ? 2 : 3;
+    static_assert((BAMG_WAVE >> SH) == K, "K must be 8, 16, 32 or 64");
     const int lane = threadIdx.x % BAMG_WAVE, wv = threadIdx.x / BAMG_WAVE;
-    const int i0 = g.off + blockIdx.x * seg_rows, i1 = min(g.off + g.n, i0 + seg_rows);
-    if (i0 >= i1) return;
-    const double* hc = h + (size_t)blockIdx.y * HS;
-    double acc[MAXB];
+    wave_sum_many<K>(acc);
+    ey = wave_sum(ey);
+    ex = wave_sum(ex);
+    if ((lane & ((1 << SH) - 1)) == 0) red[wv * (K + 2) + (lane >> SH)] = acc[0];
+    if (lane == 0) { red[wv * (K + 2) + K] = ey; red[wv * (K + 2) + K + 1] = ex; }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < nb + 2) {
+        const int src = t < nb ? t : K + (t - nb);
+        double v = 0;
 #pragma unroll
-    for (int b = 0; b < MAXB; ++b) acc[b] = 0.0;
-    for (int i = i0 + threadIdx.x; i < i1; i += BAMG_BLK) {
-        double v[MAXB];
-#pragma unroll
-        for (int b = 0; b < MAXB; ++b) v[b] = b < nb ? V[(size_t)b * N + i] : 0.0;
-        double s = w[i];
-#pragma unroll
-        for (int b = 0; b < MAXB; ++b)
-            if (b < nb) s -= hc[b] * v[b];
-        w[i] = s;
-#pragma unroll
-        for (int b = 0; b < MAXB; ++b)
-            if (b < nb) acc[b] += v[b] * s;
-    }
-    const size_t slot = (((size_t)blockIdx.y * gridDim.x + blockIdx.x) * (BAMG_BLK / BAMG_WAVE) + wv) * nb;
-#pragma unroll
-    for (int b = 0; b < MAXB; ++b) {
-        if (b < nb) {
-            const double t = wave_sum(acc[b]);
-            if (lane == 0) part[slot + b] = t;
-        }
+        for (int q = 0; q < BAMG_BLK / BAMG_WAVE; ++q) v += red[q * (K + 2) + src];
+        part[((size_t)blockIdx.y * NDM + t) * gridDim.x + blockIdx.x] = v;
     }
 }
 
-// k_seg_upd_norm: w <- w - sum_{b<nb} h_b V_b on chains with act2 (the second
-// pass where it is needed), then the partial ||w||^2 of every chain with act
-// (one value per wave, nv = 1 layout).
+// Dots pass: <q_b, w> (b < nb), <v_nb, w>, <w, w> on a chunk of one chain.
+// K >= nb accumulators per thread; grid (chunks, chains).
+template <int K>
 __global__ void __launch_bounds__(BAMG_BLK)
-k_seg_upd_norm(const ChainGeo* __restrict__ geo, int seg_rows, int N, int nb, const int* __restrict__ act,
-               const int* __restrict__ act2, const double* __restrict__ V, const double* __restrict__ h, int HS,
-               double* __restrict__ w, double* __restrict__ part) {
+k_gs_dots(const ChainGeo* __restrict__ geo, int seg_rows, int N, int nb, const int* __restrict__ act,
+          const double* __restrict__ V, const double* __restrict__ w, double* __restrict__ part, int NDM) {
+    __shared__ double red[(BAMG_BLK / BAMG_WAVE) * (K + 2)];
     const ChainGeo g = geo[blockIdx.y];
     if (!act[blockIdx.y]) return;
-    const bool upd = act2[blockIdx.y] != 0;
-    const int lane = threadIdx.x % BAMG_WAVE, wv = threadIdx.x / BAMG_WAVE;
     const int i0 = g.off + blockIdx.x * seg_rows, i1 = min(g.off + g.n, i0 + seg_rows);
     if (i0 >= i1) return;
-    const double* hc = h + (size_t)blockIdx.y * HS;
-    double acc = 0.0;
+    const double* y = V + (size_t)nb * N;
+    double acc[K];
+#pragma unroll
+    for (int b = 0; b < K; ++b) acc[b] = 0.0;
+    double ey = 0.0, ex = 0.0;
     for (int i = i0 + threadIdx.x; i < i1; i += BAMG_BLK) {
-        double s = w[i];
-        if (upd) {
-            for (int b = 0; b < nb; ++b) s -= hc[b] * V[(size_t)b * N + i];
-            w[i] = s;
-        }
-        acc += s * s;
+        const double x = w[i];
+#pragma unroll
+        for (int b = 0; b < K; ++b)
+            if (b < nb) acc[b] += V[(size_t)b * N + i] * x;
+        ey += y[i] * x;
+        ex += x * x;
     }
-    acc = wave_sum(acc);
-    if (lane == 0) part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * (BAMG_BLK / BAMG_WAVE) + wv] = acc;
+    gs_store_partials<K>(acc, ey, ex, nb, part, NDM, red);
 }
 
-// out[c * stride] = sum of chain c's wave partials (its own chunk count, P
-// chunks per chain) for chains with act; one block per chain.
-__global__ void k_seg_wave_final(const ChainGeo* __restrict__ geo, int seg_rows, int P, const int* __restrict__ act,
-                                 const double* __restrict__ part, double* __restrict__ out, int stride) {
+// Update pass on a chunk of one chain, with the coefficients of k_gs_step
+// (cf = coef + c GS_CS: [b] a_b, [GS_MAXB + b] d_b, [2 GS_MAXB] 1/alpha,
+// [+1] h, [+2] 1/nu):  q_nb = (v_nb - sum a_b q_b) / alpha over V_nb (not
+// rewritten for nb = 0, where v_0 is exact), v_{nb+1} = (w - sum d_b q_b -
+// h q_nb) / nu into V_{nb+1}, then the dots of v_{nb+1}.  The q_b of a row
+// are loaded once into registers (K >= nb) for the updates and the dots.
+template <int K>
+__global__ void __launch_bounds__(BAMG_BLK)
+k_gs_update(const ChainGeo* __restrict__ geo, int seg_rows, int N, int nb, const int* __restrict__ act,
+            double* __restrict__ V, const double* __restrict__ w, const double* __restrict__ coef,
+            double* __restrict__ part, int NDM) {
+    __shared__ double red[(BAMG_BLK / BAMG_WAVE) * (K + 2)];
+    const ChainGeo g = geo[blockIdx.y];
+    if (!act[blockIdx.y]) return;
+    const int i0 = g.off + blockIdx.x * seg_rows, i1 = min(g.off + g.n, i0 + seg_rows);
+    if (i0 >= i1) return;
+    const double* cf = coef + (size_t)blockIdx.y * GS_CS;
+    const double ia = cf[2 * GS_MAXB], hh = cf[2 * GS_MAXB + 1], inu = cf[2 * GS_MAXB + 2];
+    double* y = V + (size_t)nb * N;
+    double* xn = V + (size_t)(nb + 1) * N;
+    double acc[K];
+#pragma unroll
+    for (int b = 0; b < K; ++b) acc[b] = 0.0;
+    double ey = 0.0, ex = 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += BAMG_BLK) {
+        double q[K];
+#pragma unroll
+        for (int b = 0; b < K; ++b) q[b] = b < nb ? V[(size_t)b * N + i] : 0.0;
+        double t = y[i];
+#pragma unroll
+        for (int b = 0; b < K; ++b)
+            if (b < nb) t -= cf[b] * q[b];
+        t *= ia;
+        if (nb > 0) y[i] = t;
+        double x = w[i];
+#pragma unroll
+        for (int b = 0; b < K; ++b)
+            if (b < nb) x -= cf[GS_MAXB + b] * q[b];
+        x = (x - hh * t) * inu;
+        xn[i] = x;
+#pragma unroll
+        for (int b = 0; b < K; ++b)
+            if (b < nb) acc[b] += q[b] * x;
+        ey += t * x;
+        ex += x * x;
+    }
+    gs_store_partials<K>(acc, ey, ex, nb, part, NDM, red);
+}
+
+// out[c OS + d] = sum of chain c's chunk values of dot d, in chunk order.
+// Grid (dots, chains); P = chunks per chain slot (the passes' grid x).
+__global__ void k_gs_final(const ChainGeo* __restrict__ geo, int seg_rows, int P, const int* __restrict__ act,
+                           const double* __restrict__ part, int NDM, double* __restrict__ out, int OS) {
     __shared__ double sh[BAMG_BLK / BAMG_WAVE];
-    const int c = blockIdx.x;
+    const int d = blockIdx.x, c = blockIdx.y;
     if (!act[c]) return;
-    const int WPB = BAMG_BLK / BAMG_WAVE;
-    const int np = ((geo[c].n + seg_rows - 1) / seg_rows) * WPB;
+    const int np = (geo[c].n + seg_rows - 1) / seg_rows;
+    const double* pp = part + ((size_t)c * NDM + d) * P;
     double s = 0;
-    for (int j = threadIdx.x; j < np; j += BAMG_BLK) s += part[(size_t)c * P * WPB + j];
+    for (int k = threadIdx.x; k < np; k += BAMG_BLK) s += pp[k];
     s = block_sum(s, sh);
-    if (threadIdx.x == 0) out[(size_t)c * stride] = s;
-}
-
-// w -= sum_b h_b V_b on the rows of active chains.
-__global__ void k_seg_vupdate(int N, const ChainGeo* __restrict__ geo, int nch, int nv, const int* __restrict__ act,
-                              const double* __restrict__ V, const double* __restrict__ h, int HS,
-                              double* __restrict__ w) {
-    int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
-    if (i >= N) return;
-    const int c = find_chain(geo, nch, i);
-    if (!act[c]) return;
-    const double* hc = h + (size_t)c * HS;
-    double s = w[i];
-    for (int b = 0; b < nv; ++b) s -= hc[b] * V[(size_t)b * N + i];
-    w[i] = s;
+    if (threadIdx.x == 0) out[(size_t)c * OS + d] = s;
 }
 
 // out_i = a_i * num_c / den_c (den_c square-rooted when sqrt_den) on the
@@ -442,30 +404,95 @@ __global__ void k_seg_scale(int N, const ChainGeo* __restrict__ geo, int nch, co
     out[i] = a[i] * s;
 }
 
-// Givens step j for every active chain (one thread each); est[c] = |g_{j+1}|.
-__global__ void k_seg_givens(int nch, int j, int ld, const int* __restrict__ act, double* __restrict__ Hall, int HS,
-                             const double* __restrict__ hnew2, int hstride, double* __restrict__ csall,
-                             double* __restrict__ snall, double* __restrict__ gall, int GS, double* __restrict__ est) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
+// Step j of the Arnoldi process for every active chain (one thread each).
+// dv = dots of the update pass that made v_j (a_b = dv[b], b < j; beta =
+// dv[j]; unused for j = 0, where v_0 is exact), dw = dots of w (d_b, b < j;
+// <v_j, w> = dw[j]; <w, w> = dw[j + 1]).  Per chain, aux holds nu_k (the norm
+// estimate that made v_{k+1}), then xr_k and gr_k (row k of column k and g_k
+// before Givens rotation k), GS entries each.
+//  1. alpha = sqrt(beta - |a|^2) finishes v_j; column j-1 of H becomes
+//     h + nu_{j-1} a with subdiagonal nu_{j-1} alpha: the change is rotated by
+//     the rotations 0 .. j-2, and rotation j-1 and g_{j-1}, g_j are redone.
+//  2. Column j: d_b (b < j), h_j = (<v_j, w> - a.d) / alpha, and the norm
+//     estimate nu_j^2 = <w, w> - |d|^2 - h_j^2 (Pythagoras: one pass of
+//     classical Gram-Schmidt against orthonormal q), rotated as usual;
+//     est[c] = |g_{j+1}|.
+//  3. The update pass's coefficients go to coef + c GS_CS.
+// alpha = 0 (v_j inside the span: a breakdown) empties column j and ends the
+// chain's inner iteration (est = 0, g_j = 0).
+__global__ void k_gs_step(int nch, int j, int ld, const int* __restrict__ act, const double* __restrict__ dvall,
+                          const double* __restrict__ dwall, int DS, double* __restrict__ Hall, int HS,
+                          double* __restrict__ csall, double* __restrict__ snall, double* __restrict__ gall,
+                          double* __restrict__ auxall, int GS, double* __restrict__ coefall, double* __restrict__ est) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nch || !act[c]) return;
-    double* col = Hall + (size_t)c * HS + (size_t)j * ld;
+    const double* a = dvall + (size_t)c * DS;
+    const double* d = dwall + (size_t)c * DS;
+    double* H = Hall + (size_t)c * HS;
     double* cs = csall + (size_t)c * GS;
     double* sn = snall + (size_t)c * GS;
     double* g = gall + (size_t)c * GS;
-    col[j + 1] = sqrt(hnew2[(size_t)c * hstride]);
-    for (int i = 0; i < j; ++i) {
-        double a = col[i], b = col[i + 1];
-        col[i] = cs[i] * a + sn[i] * b;
-        col[i + 1] = -sn[i] * a + cs[i] * b;
+    double* nu = auxall + (size_t)c * 3 * GS;
+    double* xr = nu + GS;
+    double* gr = xr + GS;
+    double* cf = coefall + (size_t)c * GS_CS;
+    double alpha = 1.0, hj, ad = 0.0;
+    bool broke = false;
+    if (j > 0) {
+        double s2 = 0.0;
+        for (int b = 0; b < j; ++b) { s2 += a[b] * a[b]; ad += a[b] * d[b]; }
+        const double al2 = a[j] - s2;
+        alpha = al2 > 0.0 ? sqrt(al2) : 0.0;
+        broke = !(alpha > 0.0);
+        double* cp = H + (size_t)(j - 1) * ld;
+        const double np = nu[j - 1];
+        double carry = np * a[0];
+        for (int i = 0; i + 1 < j; ++i) {
+            const double nx = np * a[i + 1];
+            cp[i] += cs[i] * carry + sn[i] * nx;
+            carry = -sn[i] * carry + cs[i] * nx;
+        }
+        const double x = xr[j - 1] + carry, yv = np * alpha;
+        const double r = sqrt(x * x + yv * yv);
+        const double cc = r > 0.0 ? x / r : 1.0, ss = r > 0.0 ? yv / r : 0.0;
+        cp[j - 1] = r > 0.0 ? r : 1.0;
+        cp[j] = 0.0;
+        cs[j - 1] = cc; sn[j - 1] = ss;
+        g[j - 1] = cc * gr[j - 1];
+        g[j] = -ss * gr[j - 1];
+        hj = broke ? 0.0 : (d[j] - ad) / alpha;
+    } else {
+        hj = d[0];
     }
-    double a = col[j], b = col[j + 1];
-    double r = sqrt(a * a + b * b);
-    double cc = r > 0 ? a / r : 1.0, s = r > 0 ? b / r : 0.0;
-    cs[j] = cc; sn[j] = s;
-    col[j] = r; col[j + 1] = 0.0;
-    g[j + 1] = -s * g[j];
+    double* col = H + (size_t)j * ld;
+    double nu2 = d[j + 1] - hj * hj;
+    for (int b = 0; b < j; ++b) {
+        col[b] = broke ? 0.0 : d[b];
+        nu2 -= d[b] * d[b];
+    }
+    col[j] = hj;
+    const double nuj = (!broke && nu2 > 0.0) ? sqrt(nu2) : 0.0;
+    for (int i = 0; i < j; ++i) {
+        const double u = col[i], v = col[i + 1];
+        col[i] = cs[i] * u + sn[i] * v;
+        col[i + 1] = -sn[i] * u + cs[i] * v;
+    }
+    xr[j] = col[j];
+    gr[j] = g[j];
+    nu[j] = nuj;
+    const double x = col[j];
+    const double r = sqrt(x * x + nuj * nuj);
+    const double cc = r > 0.0 ? x / r : 1.0, ss = r > 0.0 ? nuj / r : 0.0;
+    col[j] = r > 0.0 ? r : 1.0;
+    col[j + 1] = 0.0;
+    cs[j] = cc; sn[j] = ss;
+    g[j + 1] = -ss * g[j];
     g[j] = cc * g[j];
-    est[c] = fabs(g[j + 1]);
+    est[c] = broke ? 0.0 : fabs(g[j + 1]);
+    for (int b = 0; b < j; ++b) { cf[b] = a[b]; cf[GS_MAXB + b] = d[b]; }
+    cf[2 * GS_MAXB] = 1.0 / alpha;
+    cf[2 * GS_MAXB + 1] = hj;
+    cf[2 * GS_MAXB + 2] = nuj > 0.0 ? 1.0 / nuj : 0.0;
 }
 
 // g = [beta_c, 0, ...] for every chain (beta2 per chain at stride).
@@ -477,7 +504,6 @@ __global__ void k_seg_gmres_init(int nch, int m, const double* __restrict__ beta
     if (threadIdx.x == 0) gall[(size_t)c * GS] = sqrt(beta2[(size_t)c * stride]);
 }
 
-// Back substitution per chain with its own k = kd[c].
 __global__ void k_seg_gmres_y(int nch, int ld, const int* __restrict__ kd, const double* __restrict__ Hall, int HS,
                               const double* __restrict__ gall, int GS, double* __restrict__ yall) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
