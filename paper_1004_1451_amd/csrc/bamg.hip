@@ -307,7 +307,7 @@ struct Engine : bamg_ctx {
     static constexpr bool MIXED = sizeof(T) == 4;
     Arena A;
     std::vector<Level<T>> L;
-    int VS = 7;                      // row stride of the eigenvector blocks
+    int VS = 8;                      // row stride of the eigenvector blocks (a multiple of 4)
     // finest level in FP64 for the outer iteration
     int* b0rp = nullptr;
     int* b0ci = nullptr;
@@ -465,7 +465,7 @@ struct Engine : bamg_ctx {
 
     void allocate(int nnzA) {
         const int depth = (int)L.size();
-        VS = std::max(1, o.n_eig) + 1;
+        VS = (std::max(1, o.n_eig) + 1 + 3) / 4 * 4;     // padded for 16-byte row moves
         for (int l = 0; l < depth; ++l) {
             auto& lv = L[l];
             const int n_l = lv.rows;
@@ -744,8 +744,9 @@ struct Engine : bamg_ctx {
     void tv_weights(int l, int use_v) {
         auto& lv = L[l];
         dim3 grid(lv.cnp, lv.ncont);
-        hipLaunchKernelGGL((k_colnorm_partial<T, T>), grid, dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo, CN_ROWS,
-                           r, use_v,
+        auto part_k = r % 4 == 0 ? k_colnorm_partial<T, T, 4>
+                    : r % 2 == 0 ? k_colnorm_partial<T, T, 2> : k_colnorm_partial<T, T, 1>;
+        hipLaunchKernelGGL(part_k, grid, dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo, CN_ROWS, r, use_v,
                            (const int*)nvc, VS, lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const T*)lv.U, (const T*)lv.V,
                            WS, part);
         HIPCHK(hipGetLastError());
@@ -983,10 +984,11 @@ struct Engine : bamg_ctx {
             LAUNCH((k_interp<T, T>), nblk(tot), BAMG_BLK, s, rows, VS, dR, lv.pc, (const T*)lv.pv, (const T*)c.V, lv.V);
             T* a = lv.V;
             T* b = sweep_tmp;
+            auto relax = VS == 4 ? k_eig_relax<T, T, 4> : VS == 8 ? k_eig_relax<T, T, 8> : k_eig_relax<T, T, 12>;
             for (int k = 0; k < o.nu_setup; ++k) {
-                LAUNCH((k_eig_relax<T, T>), nblk(tot), BAMG_BLK, s, rows, (const ChainGeo*)lv.dgeo, lv.ncont, VS, dR,
-                       (const int*)nvc, KV, lv.B.rp, lv.B.ci, (const T*)lv.B.v, lv.Tm.rp, lv.Tm.ci, (const T*)lv.Tm.v,
-                       (const double*)lam, (const int*)kind, o.omega, (const T*)a, b);
+                LAUNCH(relax, nblk(rows), BAMG_BLK, s, rows, (const ChainGeo*)lv.dgeo, lv.ncont, (const int*)nvc, KV,
+                       lv.B.rp, lv.B.ci, (const T*)lv.B.v, lv.Tm.rp, lv.Tm.ci, (const T*)lv.Tm.v, (const double*)lam,
+                       (const int*)kind, o.omega, (const T*)a, b);
                 std::swap(a, b);
             }
             if (a != lv.V) HIPCHK(hipMemcpyAsync(lv.V, a, sizeof(T) * tot, hipMemcpyDeviceToDevice, s));

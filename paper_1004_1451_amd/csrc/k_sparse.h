@@ -308,50 +308,73 @@ __global__ void k_interp(int n, int R, FastDiv divR, const int* __restrict__ pc,
 // ---------------------------------------------------------------- TV weights
 // Stage 1, per chain (blockIdx.y) and row chunk of seg_rows (blockIdx.x):
 // partial sums of (B x_k)_i^2 and (x_k)_i^2 for the chain's columns k of
-// X = [U | V] (U: Ru columns, ld Ru; V: nv_c columns, ld VS; V unused when
-// use_v == 0).  Thread layout as in the sweep: R = Ru + nv_c slots per row,
-// BAMG_BLK / R rows per pass (thread t: row t / R, column t % R); each
-// thread keeps its own column's sums, then one thread per column adds them
-// in thread order.  part: [chain][chunk][2 * WS].
-template <typename T, typename M>
+// X = [U | V] (U: Ru columns, ld Ru; V: ld VS, a multiple of 4, unused when
+// use_v == 0).  A thread takes VW adjacent columns of one row (VW divides Ru
+// and VS; G groups per row, BAMG_BLK / G rows per pass), walks the row's
+// entries once and moves its columns with one vector load per neighbour;
+// then, per column, one thread adds the per-thread sums in row order.
+// part[((c 2 WS) + k) P + chunk] = sum of (B x_k)^2, [.. + WS + k ..] = sum
+// of x_k^2 (P = chunks per chain slot), for the chain's used columns only.
+template <typename T, typename M, int VW>
 __global__ void __launch_bounds__(BAMG_BLK)
 k_colnorm_partial(const ChainGeo* __restrict__ geo, int seg_rows, int Ru, int use_v, const int* __restrict__ nvc,
                   int VS, const int* __restrict__ rp, const int* __restrict__ ci, const M* __restrict__ v,
                   const T* __restrict__ U, const T* __restrict__ V, int WS, double* __restrict__ part) {
-    __shared__ double sr[BAMG_BLK], sx[BAMG_BLK];
+    __shared__ double sr[BAMG_BLK * VW], sx[BAMG_BLK * VW];
     const int c = blockIdx.y;
     const ChainGeo g = geo[c];
-    const int R = Ru + (use_v ? nvc[c] : 0);
+    const int GU = Ru / VW, G = GU + (use_v ? VS / VW : 0);
     const int r0 = g.off + blockIdx.x * seg_rows, r1 = min(g.off + g.n, r0 + seg_rows);
     if (r0 >= r1) return;                 // beyond this chain's own chunks
-    const int t = threadIdx.x, rpp = BAMG_BLK / R, dr = t / R, k = t - dr * R;
-    const bool inU = k < Ru;
+    const int t = threadIdx.x, rpp = BAMG_BLK / G, dr = t / G, kg = t - dr * G;
+    const bool inU = kg < GU;
     const T* __restrict__ X = inU ? U : V;
-    const int ld = inU ? Ru : VS, kx = inU ? k : k - Ru;
-    double ar = 0, ax = 0;
+    const int ld = inU ? Ru : VS, kx = (inU ? kg : kg - GU) * VW;
+    double ar[VW], ax[VW];
+#pragma unroll
+    for (int q = 0; q < VW; ++q) { ar[q] = 0.0; ax[q] = 0.0; }
     if (dr < rpp) {
         for (int i = r0 + dr; i < r1; i += rpp) {
-            double acc = 0;
+            double acc[VW];
+#pragma unroll
+            for (int q = 0; q < VW; ++q) acc[q] = 0.0;
             const int p1 = rp[i + 1];
-            for (int p = rp[i]; p < p1; ++p) acc += (double)v[p] * (double)X[(size_t)ci[p] * ld + kx];
-            const double xi = (double)X[(size_t)i * ld + kx];
-            ar += acc * acc;
-            ax += xi * xi;
+            for (int p = rp[i]; p < p1; ++p) {
+                const double b = (double)v[p];
+                T x[VW];
+                VecIO<T, VW>::ld(X + (size_t)ci[p] * ld + kx, x);
+#pragma unroll
+                for (int q = 0; q < VW; ++q) acc[q] += b * (double)x[q];
+            }
+            T xi[VW];
+            VecIO<T, VW>::ld(X + (size_t)i * ld + kx, xi);
+#pragma unroll
+            for (int q = 0; q < VW; ++q) {
+                ar[q] += acc[q] * acc[q];
+                ax[q] += (double)xi[q] * (double)xi[q];
+            }
         }
     }
-    sr[t] = ar;
-    sx[t] = ax;
+#pragma unroll
+    for (int q = 0; q < VW; ++q) { sr[t * VW + q] = ar[q]; sx[t * VW + q] = ax[q]; }
     __syncthreads();
-    if (t < R) {
+    if (t < G * VW) {
+        const int kgt = t / VW, q = t - kgt * VW;
         double a = 0, b = 0;
-        for (int q = t; q < rpp * R; q += R) { a += sr[q]; b += sx[q]; }
-        double* out = part + ((size_t)c * gridDim.x + blockIdx.x) * 2 * WS;
-        out[t] = a;
-        out[WS + t] = b;
+        for (int d2 = 0; d2 < rpp; ++d2) {
+            a += sr[(d2 * G + kgt) * VW + q];
+            b += sx[(d2 * G + kgt) * VW + q];
+        }
+        const int k = kgt < GU ? t : Ru + (t - GU * VW);
+        const int Rc = Ru + (use_v ? nvc[c] : 0);
+        if (k < Rc) {
+            part[((size_t)c * 2 * WS + k) * gridDim.x + blockIdx.x] = a;
+            part[((size_t)c * 2 * WS + WS + k) * gridDim.x + blockIdx.x] = b;
+        }
     }
 }
 
-// Stage 2: block (chain c, column k) adds the chunk partials in order;
+// Stage 2: block (column k, chain c) adds the chunk partials in order;
 // w_k = 1 / max(||B x_k||^2, (1e-14 ||x_k||)^2) (Section 3.2).
 __global__ void k_colnorm_final(const ChainGeo* __restrict__ geo, int seg_rows, int P, int Ru, int use_v,
                                 const int* __restrict__ nvc, int WS, const double* __restrict__ part,
@@ -361,11 +384,12 @@ __global__ void k_colnorm_final(const ChainGeo* __restrict__ geo, int seg_rows, 
     const int R = Ru + (use_v ? nvc[c] : 0);
     if (k >= R) return;
     const int nchunks = (geo[c].n + seg_rows - 1) / seg_rows;
+    const double* pa = part + ((size_t)c * 2 * WS + k) * P;
+    const double* pb = part + ((size_t)c * 2 * WS + WS + k) * P;
     double a = 0, b = 0;
     for (int j = threadIdx.x; j < nchunks; j += BAMG_BLK) {
-        const double* p = part + ((size_t)c * P + j) * 2 * WS;
-        a += p[k];
-        b += p[WS + k];
+        a += pa[j];
+        b += pb[j];
     }
     a = block_sum(a, sh);
     b = block_sum(b, sh);
@@ -861,60 +885,89 @@ k_galerkin_numeric(int nc, const ChainGeo* __restrict__ geoc, int nch,
 
 // ---------------------------------------------------------------- up-leg
 // One omega-Jacobi sweep on (B - lam_c T) x_c = 0 for every column c of the
-// eigenvector block V (row stride R), one thread per (row, column) with the
-// chain's first nvc columns in use.  kind[c]: 0 real column with real lam,
-// 1 / 2 real / imaginary part of a complex pair x = V_c + i V_{c+1} (lam
-// complex; both columns of a pair form (B - lam T) x, each keeps its own
+// eigenvector block V (row stride VP, a multiple of 4), one thread per row
+// with all VP columns: every stored entry of the row is read once and its
+// neighbour's VP values are moved with 16-byte loads; the chain's first nvc
+// columns are relaxed and the others copied.  kind[c]: 0 real column with
+// real lam, 1 / 2 real / imaginary part of a complex pair x = V_c + i V_{c+1}
+// (lam complex; both columns of a pair form (B - lam T) x, each keeps its own
 // part); D_lam = diag(B) - lam diag(T).  T == identity when trp is null.
-// Column 0 (the null-vector approximation) has lam = 0.
-template <typename T, typename M>
+// Column 0 (the null-vector approximation) has lam = 0.  Products are added
+// in CSR order in FP64.
+template <typename T, typename M, int VP>
 __global__ void __launch_bounds__(BAMG_BLK)
-k_eig_relax(int n, const ChainGeo* __restrict__ geo, int nch, int R, FastDiv divR, const int* __restrict__ nvc,
-            int KV, const int* __restrict__ brp, const int* __restrict__ bci, const M* __restrict__ bv,
+k_eig_relax(int n, const ChainGeo* __restrict__ geo, int nch, const int* __restrict__ nvc, int KV,
+            const int* __restrict__ brp, const int* __restrict__ bci, const M* __restrict__ bv,
             const int* __restrict__ trp, const int* __restrict__ tci, const M* __restrict__ tv,
             const double* __restrict__ lamall, const int* __restrict__ kindall, double omega,
             const T* __restrict__ X, T* __restrict__ Y) {
-    const long long tt = (long long)xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
-    if (tt >= (long long)n * R) return;
-    const int i = (int)divR.div((uint32_t)tt), c = (int)(tt - (long long)i * R);
+    static_assert(VP % 4 == 0, "row stride must be a multiple of 4");
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
     const int ch = find_chain(geo, nch, i);
-    if (c >= nvc[ch]) return;
-    const int k = kindall[(size_t)ch * KV + c];
-    const double lr = lamall[(size_t)ch * 2 * KV + 2 * c], li = lamall[(size_t)ch * 2 * KV + 2 * c + 1];
-    const int ca = k == 2 ? c - 1 : c;            // real-part column of the pair
-    const bool pair = k != 0;
-    double b0 = 0, b1 = 0, t0 = 0, t1 = 0, bd = 0, td = trp ? 0.0 : 1.0;
+    const int nv = nvc[ch];
+    auto load = [&](int row, T (&x)[VP]) {
+#pragma unroll
+        for (int k = 0; k < VP; k += 4) VecIO<T, 4>::ld(X + (size_t)row * VP + k, x + k);
+    };
+    double bs[VP], ts[VP];
+#pragma unroll
+    for (int c = 0; c < VP; ++c) { bs[c] = 0.0; ts[c] = 0.0; }
+    double bd = 0, td = trp ? 0.0 : 1.0;
     for (int p = brp[i]; p < brp[i + 1]; ++p) {
         const int j = bci[p];
         const double b = (double)bv[p];
         if (j == i) bd = b;
-        b0 += b * (double)X[(size_t)j * R + ca];
-        if (pair) b1 += b * (double)X[(size_t)j * R + ca + 1];
+        T x[VP];
+        load(j, x);
+#pragma unroll
+        for (int c = 0; c < VP; ++c) bs[c] += b * (double)x[c];
     }
+    T xo[VP];
+    load(i, xo);
     if (trp) {
         for (int p = trp[i]; p < trp[i + 1]; ++p) {
             const int j = tci[p];
             const double t = (double)tv[p];
             if (j == i) td = t;
-            t0 += t * (double)X[(size_t)j * R + ca];
-            if (pair) t1 += t * (double)X[(size_t)j * R + ca + 1];
+            T x[VP];
+            load(j, x);
+#pragma unroll
+            for (int c = 0; c < VP; ++c) ts[c] += t * (double)x[c];
         }
     } else {
-        t0 = (double)X[(size_t)i * R + ca];
-        if (pair) t1 = (double)X[(size_t)i * R + ca + 1];
+#pragma unroll
+        for (int c = 0; c < VP; ++c) ts[c] = (double)xo[c];
     }
-    const double xo = (double)X[(size_t)i * R + c];
-    if (!pair) {
-        Y[(size_t)i * R + c] = (T)(xo - omega * (b0 - lr * t0) / (bd - lr * td));
-    } else {
-        // r = (B - lam T) x, D = bd - lam td, correction r / D
-        const double rr = (b0 - lr * t0) + li * t1;
-        const double ri = (b1 - lr * t1) - li * t0;
-        const double dr = bd - lr * td, di = -li * td;
-        const double den = dr * dr + di * di;
-        const double q = k == 1 ? (rr * dr + ri * di) / den : (ri * dr - rr * di) / den;
-        Y[(size_t)i * R + c] = (T)(xo - omega * q);
+    const int* kind = kindall + (size_t)ch * KV;
+    const double* lam = lamall + (size_t)ch * 2 * KV;
+    T out[VP];
+#pragma unroll
+    for (int c = 0; c < VP; ++c) {
+        out[c] = xo[c];
+        if (c >= nv) continue;
+        const int k = kind[c];
+        const double lr = lam[2 * c], li = lam[2 * c + 1];
+        if (k == 0) {
+            out[c] = (T)((double)xo[c] - omega * (bs[c] - lr * ts[c]) / (bd - lr * td));
+        } else {
+            // the pair's real and imaginary columns ca, ca + 1
+            const double b0 = k == 2 ? (c > 0 ? bs[c - 1] : 0.0) : bs[c];
+            const double b1 = k == 2 ? bs[c] : (c + 1 < VP ? bs[c + 1] : 0.0);
+            const double t0 = k == 2 ? (c > 0 ? ts[c - 1] : 0.0) : ts[c];
+            const double t1 = k == 2 ? ts[c] : (c + 1 < VP ? ts[c + 1] : 0.0);
+            // r = (B - lam T) x, D = bd - lam td, correction r / D
+            const double rr = (b0 - lr * t0) + li * t1;
+            const double ri = (b1 - lr * t1) - li * t0;
+            const double dr = bd - lr * td, di = -li * td;
+            const double den = dr * dr + di * di;
+            const double q = k == 1 ? (rr * dr + ri * di) / den : (ri * dr - rr * di) / den;
+            out[c] = (T)((double)xo[c] - omega * q);
+        }
     }
+    T* y = Y + (size_t)i * VP;
+#pragma unroll
+    for (int k = 0; k < VP; k += 4) VecIO<T, 4>::st(y + k, out + k);
 }
 
 // Rayleigh quotient partials, per chain (blockIdx.y) and row chunk of
