@@ -501,13 +501,7 @@ __device__ __forceinline__ void ls_point(int i, const ChainGeo& g, int ia, int i
         const int ld = part == 0 ? Ru : VS;
         const int nk = part == 0 ? Ru : Rv;
         const double* wp = w + (part == 0 ? 0 : Ru);
-#pragma unroll 2
-        for (int kk = 0; kk < nk; ++kk) {
-            double wk = wp[kk];
-            double xi = (double)Xp[(size_t)i * ld + kk];
-            double xs[4];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) xs[s] = ((valid >> s) & 1) ? (double)Xp[(size_t)P.sf[s] * ld + kk] : 0.0;
+        auto accumulate = [&](double wk, double xi, const double (&xs)[4]) {
             sigma += wk * xi * xi;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
@@ -516,6 +510,36 @@ __device__ __forceinline__ void ls_point(int i, const ChainGeo& g, int ia, int i
 #pragma unroll
                 for (int t = 0; t <= s; ++t) P.G[s][t] += ws * xs[t];
             }
+        };
+        if (ld % 4 == 0) {
+            // four columns per 16-byte load (rows are 4-aligned); same order
+            for (int k0 = 0; k0 < nk; k0 += 4) {
+                T xi4[4], xs4[4][4];
+                VecIO<T, 4>::ld(Xp + (size_t)i * ld + k0, xi4);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    if ((valid >> s) & 1) VecIO<T, 4>::ld(Xp + (size_t)P.sf[s] * ld + k0, xs4[s]);
+                    else
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) xs4[s][q] = (T)0;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (k0 + q >= nk) break;
+                    double xs[4];
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) xs[s] = (double)xs4[s][q];
+                    accumulate(wp[k0 + q], (double)xi4[q], xs);
+                }
+            }
+        } else {
+#pragma unroll 2
+            for (int kk = 0; kk < nk; ++kk) {
+                double xs[4];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) xs[s] = ((valid >> s) & 1) ? (double)Xp[(size_t)P.sf[s] * ld + kk] : 0.0;
+                accumulate(wp[kk], (double)Xp[(size_t)i * ld + kk], xs);
+            }
         }
     }
 #pragma unroll
@@ -523,12 +547,43 @@ __device__ __forceinline__ void ls_point(int i, const ChainGeo& g, int ia, int i
 #pragma unroll
         for (int t = s + 1; t < 4; ++t) P.G[s][t] = P.G[t][s];
     P.sigma = sigma;
-    // greedy selection (Algorithm 2)
+    // greedy selection (Algorithm 2).  When every slot stays admissible
+    // whatever else is selected, the selection is all slots: the pivot a
+    // candidate g gets after J, s(g | J), is at least s(g | all other slots)
+    // = 1 / (G^-1)_gg.  That case is decided from one Cholesky of the full
+    // set with a factor 100 over the admissibility bound, so rounding cannot
+    // pass a slot the greedy steps would reject; the slots are a prefix.
     int J = 0, nsel = 0;
     double L[4][4], z[4], detJ = 1.0;
+    bool all = ns > 0 && ns <= caliber;
+    if (all) {
+        double det;
+        all = chol4(P.G, P.b, valid, L, z, det);
+        double W[4][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            W[j][j] = j < ns ? 1.0 / L[j][j] : 0.0;
+#pragma unroll
+            for (int i = j + 1; i < 4; ++i) {
+                double t = 0.0;
+#pragma unroll
+                for (int k = j; k < i; ++k) t += L[i][k] * W[k][j];
+                W[i][j] = i < ns ? -t / L[i][i] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            if (g >= ns) continue;
+            double gi = 0.0;
+#pragma unroll
+            for (int k = g; k < 4; ++k) gi += W[k][g] * W[k][g];
+            all = all && (1.0 / gi > 1e-8 * P.G[g][g]);
+        }
+    }
+    if (all) { J = valid; nsel = ns; }
 #pragma unroll
     for (int step = 0; step < 4; ++step) {
-        if (nsel >= caliber) break;
+        if (all || nsel >= caliber) break;
         int best = -1;
         double bestL = 0;
 #pragma unroll
