@@ -159,6 +159,8 @@ def main():
     ap.add_argument("--no-fp64-compare", action="store_true",
                     help="skip the untimed FP64 run that the mixed result is compared with")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--relax", choices=["jacobi", "mcgs"], default="jacobi",
+                    help="tandem workload: omega-Jacobi (the paper's) or multicolour Gauss-Seidel sweeps")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run three plain device copies of MIB MiB (the reference kernel whose FETCH_SIZE / "
                          "WRITE_SIZE counters scale the traffic figures) and exit")
@@ -186,7 +188,8 @@ def main():
         ch = C.tandem_queue(args.N)
         rp, ci, v = B.device_csr(ch)
         x = torch.empty(ch.n, dtype=torch.float64, device="cuda")
-        opts = B.default_options(levels=args.levels, precision=prec, profile=1)
+        relax = B.RELAX_MCGS if args.relax == "mcgs" else B.RELAX_JACOBI
+        opts = B.default_options(levels=args.levels, precision=prec, profile=1, relax=relax)
 
         def step():
             h = B.Hierarchy(ch.n, rp, ci, v, (ch.nx, ch.ny, 0), args.r, opts)
@@ -198,8 +201,11 @@ def main():
         sec, res = _timed(step, args)
         infos = [a for a, _ in res]
         stats = [b for _, b in res]
-        sweep_ms, roof = _roofline(stats, traffic)
+        sweep_ms, roof = _roofline(stats, traffic if args.relax == "jacobi" else None)
         roof["kernel"] += ", R=%d" % args.r
+        if args.relax == "mcgs":
+            roof["kernel"] = "k_mcgs_tv<VW=%d> x colours (level-0 test-vector Gauss-Seidel sweep), R=%d" % (
+                stats[-1].sweep_vw, args.r)
         detail = _kernel_detail(stats)
         detail.update({"cycles": [i.cycles for i in infos],
                        "history": [float("%.3e" % v) for v in list(infos[-1].history)[: infos[-1].history_len]],
@@ -209,7 +215,7 @@ def main():
             # outside the timed region: the plain FP64 form, its time per step
             # and how far the mixed solution is from it
             x_mixed = x.clone()
-            opts = B.default_options(levels=args.levels, precision=B.FP64, profile=1)
+            opts = B.default_options(levels=args.levels, precision=B.FP64, profile=1, relax=relax)
             sec64, res64 = _timed(step, argparse.Namespace(warmup=1, steps=max(1, min(args.steps, 3))))
             detail["fp64_ms_per_step"] = round(sec64 * 1e3, 3)
             detail["fp64_cycles"] = res64[-1][0].cycles
@@ -220,7 +226,8 @@ def main():
             "ms_per_step": round(sec * 1e3, 3), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
             "dtype": "f64" if prec == B.FP64 else "f32+f64", "data": "synthetic",
             "config": {"workload": f"tandem queue N={args.N} (n={ch.n:,}), rates 11/31,10/31,10/31, r={args.r}, "
-                                   f"{args.levels} levels, tol {args.tol:g}", "precision": args.precision},
+                                   f"{args.levels} levels, tol {args.tol:g}", "precision": args.precision,
+                       **({"relax": "multicolour Gauss-Seidel"} if args.relax == "mcgs" else {})},
             "roofline": roof, "detail": detail,
         }
         if not args.no_cpu_baseline:

@@ -61,6 +61,22 @@ extern "C" {
 #define BAMG_MIXED 1            /* FP32 relaxation, Galerkin products and V-cycle;
                                    FP64 norms, coarsest solve and outer iteration */
 
+#define BAMG_RELAX_JACOBI 0     /* omega-Jacobi: x <- x + omega D^-1 (f - B x)    */
+#define BAMG_RELAX_MCGS 1       /* multicolour Gauss-Seidel (Section 3 names
+                                   Gauss-Seidel beside Jacobi): the points of a
+                                   level are coloured by grid position, two
+                                   colours per direction (three along a periodic
+                                   side of odd length), so no two points within
+                                   Chebyshev distance 1 share one; a sweep
+                                   updates colour 0, 1, ... in order,
+                                   x_i <- x_i + gs_omega (f_i - (B x)_i) / b_ii.
+                                   Every operator must couple only points of
+                                   different colours: bamg_setup accepts only
+                                   operators within the 3 x 3 grid box and every
+                                   coarse operator stays within it, so this
+                                   holds; each level is still checked (a
+                                   violation fails with BAMG_EINVAL).            */
+
 #define BAMG_INTERP_LS 0        /* least-squares interpolation (Algorithm 2)     */
 #define BAMG_INTERP_MLP 1       /* learned weights with the LS fit as judge      */
 
@@ -106,6 +122,10 @@ typedef struct {
     float mlp_judge;     /* learned form: keep the network's row when the LS
                             functional at it is <= mlp_judge x the fit's
                             minimum (default 2)                               */
+    int32_t relax;       /* BAMG_RELAX_JACOBI (omega-Jacobi, default) or
+                            BAMG_RELAX_MCGS (multicolour Gauss-Seidel) for the
+                            test-vector, eigenvector and cycle sweeps         */
+    double gs_omega;     /* weight of the Gauss-Seidel update (default 1)     */
 } bamg_options;
 
 typedef struct {
@@ -180,7 +200,7 @@ typedef struct {
 /* Fill *opt with the defaults: levels 0, coarse_max 1024, nu_setup 4,
    V(2,2), omega 0.7, caliber 4, n_eig 6, arnoldi_m 40, gmres_m 50,
    FP64, LS interpolation, seed 0, no budget, no profiling, 2 setup passes,
-   mlp_judge 2. */
+   mlp_judge 2, omega-Jacobi relaxation (gs_omega 1). */
 void bamg_options_default(bamg_options* opt);
 
 /* Build the hierarchy for A (device CSR, see conventions) with r initial test

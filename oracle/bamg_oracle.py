@@ -178,6 +178,69 @@ def jacobi(B: sp.csr_matrix, X: np.ndarray, omega: float, nu: int, F: np.ndarray
     return X
 
 
+# Multicolour Gauss-Seidel, the other deterministic relaxation of Section 3
+# (Gauss-Seidel is named next to Jacobi there): the points are split into
+# colours such that no two points of one colour are coupled, and one sweep
+# updates the colours in order, each colour from the latest values of the
+# others (so within a colour the order does not matter).
+# ---------------------------------------------------------------------------
+def _dir_colour(a: np.ndarray, m: int, periodic: bool) -> tuple[np.ndarray, int]:
+    """Colours of positions a along one grid direction of length m: 0 and 1
+    alternate; on a periodic direction of odd length the last position gets
+    colour 2, so neighbours a, a+1 (mod m) always differ."""
+    if periodic and m % 2 == 1 and m > 1:
+        return np.where(a == m - 1, 2, a % 2), 3
+    return a % 2, 2
+
+
+def colours(g: Grid) -> tuple[np.ndarray, int]:
+    """Colour of every state s = a*ny + b and the number of colours: the pair
+    of direction colours (ca, cb) numbered ca * (colours of b) + cb.  Two
+    distinct states within Chebyshev distance 1 differ by one step in some
+    direction, hence in that direction's colour."""
+    s = np.arange(g.n)
+    ca, na = _dir_colour(s // g.ny, g.nx, g.periodic)
+    cb, nb = _dir_colour(s % g.ny, g.ny, g.periodic)
+    return ca * nb + cb, na * nb
+
+
+def check_colouring(M: sp.csr_matrix, col: np.ndarray) -> None:
+    """Raise if an off-diagonal entry of M couples two points of one colour
+    (Gauss-Seidel by colours needs them independent)."""
+    C = sp.coo_matrix(M)
+    bad = (C.row != C.col) & (col[C.row] == col[C.col])
+    if np.any(bad):
+        raise ValueError("multicolour Gauss-Seidel: %d couplings inside one colour" % int(bad.sum()))
+
+
+def mcgs(B: sp.csr_matrix, X: np.ndarray, col: np.ndarray, ncol: int, w: float, nu: int,
+         F: np.ndarray | None = None) -> np.ndarray:
+    """nu multicolour Gauss-Seidel sweeps on B X = F (F = 0 when None): for
+    each colour c in order, x_i <- x_i + w (f_i - (B x)_i) / b_ii on the points
+    of colour c, with the current values of all other points."""
+    X = X.copy()
+    D = B.diagonal()
+    for _ in range(nu):
+        for c in range(ncol):
+            rows = np.nonzero(col == c)[0]
+            if len(rows) == 0:
+                continue
+            Bc = B[rows]
+            Rr = -(Bc @ X) if F is None else F[rows] - Bc @ X
+            d = D[rows][:, None] if X.ndim == 2 else D[rows]
+            X[rows] = X[rows] + w * Rr / d
+    return X
+
+
+def relax(lv, X: np.ndarray, opts, nu: int, F: np.ndarray | None = None) -> np.ndarray:
+    """The configured relaxation on B_l X = F: omega-Jacobi or multicolour
+    Gauss-Seidel."""
+    if opts.relax == "mcgs":
+        col, ncol = colours(lv.grid)
+        return mcgs(lv.B, X, col, ncol, opts.gs_omega, nu, F)
+    return jacobi(lv.B, X, opts.omega, nu, F)
+
+
 def tv_weights(B: sp.csr_matrix, X: np.ndarray) -> np.ndarray:
     """omega_k = 1/||B x_k||_2^2 (Section 3.2: the squared inverse of the
     residual norm of B x = 0), floored at (1e-14 ||x_k||_2)^2 so that an exact
@@ -424,11 +487,12 @@ def coarsest_eigs(B: np.ndarray, T: np.ndarray, k: int, svd=None):
 # ---------------------------------------------------------------------------
 # Up-leg eigenvector relaxation and eigenvalue update (Algorithm 3).
 # ---------------------------------------------------------------------------
-def eig_relax(B, T, V: np.ndarray, entries, omega: float, nu: int):
+def eig_relax(B, T, V: np.ndarray, entries, omega: float, nu: int, gs=None):
     """Relax (B - lam_i T) x_i = 0 with omega-Jacobi, D_lam = diag(B) -
     lam diag(T), complex arithmetic for a conjugate pair (x = Re + i Im); then
     lam_i = <B x, x>/<T x, x> = x^H B x / x^H T x for i >= 1 (lam_0 = 0 is not
-    updated).  Returns new V and entries."""
+    updated).  With gs = (colours, ncol, w) the sweeps are multicolour
+    Gauss-Seidel with weight w instead.  Returns new V and entries."""
     V = V.copy()
     dB = B.diagonal(); dT = T.diagonal()
     out = []
@@ -440,7 +504,15 @@ def eig_relax(B, T, V: np.ndarray, entries, omega: float, nu: int):
         lam = e.lam
         D = dB - lam * dT
         for _ in range(nu):
-            x = x - omega * (B @ x - lam * (T @ x)) / D
+            if gs is None:
+                x = x - omega * (B @ x - lam * (T @ x)) / D
+                continue
+            col, ncol, w = gs
+            for c in range(ncol):
+                rows = np.nonzero(col == c)[0]
+                if len(rows) == 0:
+                    continue
+                x[rows] = x[rows] - w * (B[rows] @ x - lam * (T[rows] @ x)) / D[rows]
         if e.cols != (0,):
             lam = np.vdot(x, B @ x) / np.vdot(x, T @ x)
             if len(e.cols) == 1:
@@ -469,6 +541,8 @@ class Options:
     gmres_m: int = 50
     seed: int = 0
     coarse_max: int = 1024
+    relax: str = "jacobi"      # or "mcgs": multicolour Gauss-Seidel
+    gs_omega: float = 1.0      # weight of the Gauss-Seidel update
 
 
 @dataclass
@@ -515,7 +589,9 @@ def setup(A: sp.csr_matrix, grid: Grid, r: int, opts: Options) -> Hierarchy:
     # down-leg: relax U_l, fit P_l to U_l, Galerkin products, inject U
     for l in range(len(plan) - 1):
         lv = levels[l]
-        U = jacobi(lv.B, U, opts.omega, opts.nu_setup)
+        if opts.relax == "mcgs":
+            check_colouring(lv.B, colours(lv.grid)[0])
+        U = relax(lv, U, opts, opts.nu_setup)
         lv.U = U
         P, Q, J, Bc, Tc = build_level(lv, U, opts)
         lv.P, lv.Q, lv.J = P, Q, J
@@ -532,7 +608,12 @@ def setup(A: sp.csr_matrix, grid: Grid, r: int, opts: Options) -> Hierarchy:
     for l in range(len(plan) - 2, -1, -1):
         lv = levels[l]
         V = lv.P @ V
-        V, entries = eig_relax(lv.B, lv.T, V, entries, opts.omega, opts.nu_setup)
+        gs = None
+        if opts.relax == "mcgs":
+            col, ncol = colours(lv.grid)
+            check_colouring(lv.T, col)
+            gs = (col, ncol, opts.gs_omega)
+        V, entries = eig_relax(lv.B, lv.T, V, entries, opts.omega, opts.nu_setup, gs)
         lv.V = V
     x0 = levels[0].V[:, 0] / np.sum(levels[0].V[:, 0])
     # recompute every P, B, T from the enriched sets U u V
@@ -542,6 +623,9 @@ def setup(A: sp.csr_matrix, grid: Grid, r: int, opts: Options) -> Hierarchy:
         P, Q, J, Bc, Tc = build_level(lv, X, opts)
         lv.P, lv.Q, lv.J = P, Q, J
         levels[l + 1].B, levels[l + 1].T = Bc, Tc
+    if opts.relax == "mcgs":
+        for lv in levels[:-1]:
+            check_colouring(lv.B, colours(lv.grid)[0])
     cl = levels[-1]
     Bd = cl.B.toarray()
     svd = coarsest_svd(Bd)
@@ -557,11 +641,11 @@ def vcycle(h: Hierarchy, f: np.ndarray, l: int = 0) -> np.ndarray:
     if l == len(h.levels) - 1:
         return h.pinv @ f
     o = h.opts
-    e = jacobi(lv.B, np.zeros_like(f), o.omega, o.nu_pre, F=f)
+    e = relax(lv, np.zeros_like(f), o, o.nu_pre, F=f)
     r = f - lv.B @ e
     ec = vcycle(h, lv.Q @ r, l + 1)
     e = e + lv.P @ ec
-    return jacobi(lv.B, e, o.omega, o.nu_post, F=f)
+    return relax(lv, e, o, o.nu_post, F=f)
 
 
 @dataclass

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libbamg.so")
 OK, EINVAL, ENOTSTOCH, EZERODIAG, EUNSUPPORTED, ENOMEM, EDEVICE, ENOCONV, ESINGULAR = 0, -1, -2, -3, -4, -5, -6, -7, -8
 FP64, MIXED = 0, 1
 INTERP_LS, INTERP_MLP = 0, 1
+RELAX_JACOBI, RELAX_MCGS = 0, 1
 USE_GUESS = 1
 
 X_B_ROWPTR, X_B_COL, X_B_VAL, X_T_ROWPTR, X_T_COL, X_T_VAL = 1, 2, 3, 4, 5, 6
@@ -53,7 +54,8 @@ class Options(C.Structure):
                 ("gmres_m", C.c_int32), ("precision", C.c_int32), ("interp", C.c_int32),
                 ("mlp_weights", C.c_void_p), ("seed", C.c_uint64), ("mem_budget", C.c_size_t),
                 ("profile", C.c_int32), ("stop_after", C.c_int32), ("cycle_mode", C.c_int32),
-                ("setup_passes", C.c_int32), ("collect", C.c_int32), ("mlp_judge", C.c_float)]
+                ("setup_passes", C.c_int32), ("collect", C.c_int32), ("mlp_judge", C.c_float),
+                ("relax", C.c_int32), ("gs_omega", C.c_double)]
 
 
 class SolveInfo(C.Structure):

@@ -33,6 +33,7 @@
 #include "k_coarse.h"
 #include "k_dense.h"
 #include "k_learn.h"
+#include "k_mcgs.h"
 #include "k_solve.h"
 #include "k_sparse.h"
 
@@ -308,6 +309,8 @@ struct Engine : bamg_ctx {
     Arena A;
     std::vector<Level<T>> L;
     int VS = 8;                      // row stride of the eigenvector blocks (a multiple of 4)
+    int ncol = 4;                    // colours of the multicolour Gauss-Seidel sweeps
+    bool mcgs = false;
     // finest level in FP64 for the outer iteration
     int* b0rp = nullptr;
     int* b0ci = nullptr;
@@ -455,6 +458,10 @@ struct Engine : bamg_ctx {
         }
         for (int l = 0; l + 1 < depth; ++l)
             for (int c = 0; c < L[l].ncont; ++c) L[l].geo[c].coff = L[l + 1].geo[c].off;
+        mcgs = o.relax == BAMG_RELAX_MCGS;
+        ncol = 1;
+        for (auto& lv : L)
+            for (auto& gg : lv.geo) ncol = std::max(ncol, dir_colours(gg.nx, gg.periodic) * dir_colours(gg.ny, gg.periodic));
         // fixed buffers of the cycle: the first smoothing sweep writes where the
         // parity of the remaining sweeps leaves the result in e
         for (auto& lv : L) {
@@ -721,10 +728,48 @@ struct Engine : bamg_ctx {
     }
 
     // nu homogeneous sweeps on the continuing rows of level l (R columns).
+    // Multicolour Gauss-Seidel needs every coupling of the operators of level
+    // l between points of different colours.
+    void check_colours(int l) {
+        auto& lv = L[l];
+        if (!mcgs || lv.rows == 0) return;
+        zero(err, sizeof(int) * 4);
+        LAUNCH(k_check_colours, nblk(lv.rows), BAMG_BLK, s, lv.rows, (const ChainGeo*)lv.dgeo, lv.nch,
+               (const int*)lv.B.rp, (const int*)lv.B.ci, err);
+        if (lv.Tm.rp)
+            LAUNCH(k_check_colours, nblk(lv.rows), BAMG_BLK, s, lv.rows, (const ChainGeo*)lv.dgeo, lv.nch,
+                   (const int*)lv.Tm.rp, (const int*)lv.Tm.ci, err);
+        if (get1(err))
+            fail(BAMG_EINVAL, "multicolour Gauss-Seidel: level %d couples points of one colour "
+                              "(the operator reaches beyond the 3 x 3 box)", l);
+    }
+
+    // nu multicolour Gauss-Seidel sweeps on B X = 0 for R interleaved columns.
+    void mcgs_tv(int l, T* X, int R, int nu, bool profile) {
+        auto& lv = L[l];
+        const int rows = lv.cont_rows;
+        const int vw = R % 4 == 0 ? 4 : R % 2 == 0 ? 2 : 1;
+        const int G = R / vw;
+        const FastDiv dG((uint32_t)G);
+        const long long tot = (long long)rows * G;
+        if (tot >= (1LL << 31)) fail(BAMG_EINVAL, "level %d too large for one sweep launch", l);
+        auto kern = vw == 4 ? k_mcgs_tv<T, T, 4> : vw == 2 ? k_mcgs_tv<T, T, 2> : k_mcgs_tv<T, T, 1>;
+        if (l == 0) { st.sweep_vw = vw; st.sweep_bs = BAMG_BLK; }
+        for (int k = 0; k < nu; ++k) {
+            std::pair<hipEvent_t, hipEvent_t> ev;
+            if (profile) ev = ev_begin();
+            for (int c = 0; c < ncol; ++c)
+                LAUNCH(kern, nblk(tot), BAMG_BLK, s, rows, (const ChainGeo*)lv.dgeo, lv.ncont, G, dG, c, o.gs_omega,
+                       (const int*)lv.B.rp, (const int*)lv.B.ci, (const T*)lv.B.v, X);
+            if (profile) ev_end(ev, ev_sweep);     // one sweep = every colour
+        }
+    }
+
     void sweeps(int l, T* X, int R, int nu, bool profile) {
         auto& lv = L[l];
         const int rows = lv.cont_rows;
         if (rows == 0 || nu == 0) return;
+        if (mcgs) { mcgs_tv(l, X, R, nu, profile); return; }
         T* a = X;
         T* b = sweep_tmp;
         const SweepShape sh = pick_sweep_shape(l, R, X, sweep_tmp);
@@ -804,6 +849,7 @@ struct Engine : bamg_ctx {
         LAUNCH(k_build_q<T>, nblk(c.rows), BAMG_BLK, s, c.rows, (const ChainGeo*)c.dgeo, (const ChainGeo*)lv.dgeo, c.nch,
                lv.pc, lv.qc, lv.qv, lv.qmask);
         galerkin(l, profile);
+        check_colours(l + 1);
     }
 
     // ---- coarsest pseudo-inverses of every chain into the W pool ------------
@@ -986,9 +1032,17 @@ struct Engine : bamg_ctx {
             T* b = sweep_tmp;
             auto relax = VS == 4 ? k_eig_relax<T, T, 4> : VS == 8 ? k_eig_relax<T, T, 8> : k_eig_relax<T, T, 12>;
             for (int k = 0; k < o.nu_setup; ++k) {
+                if (mcgs) {      // in place, colour by colour
+                    for (int cc = 0; cc < ncol; ++cc)
+                        LAUNCH(relax, nblk(rows), BAMG_BLK, s, rows, (const ChainGeo*)lv.dgeo, lv.ncont,
+                               (const int*)nvc, KV, lv.B.rp, lv.B.ci, (const T*)lv.B.v, lv.Tm.rp, lv.Tm.ci,
+                               (const T*)lv.Tm.v, (const double*)lam, (const int*)kind, o.gs_omega, cc,
+                               (const T*)a, a);
+                    continue;
+                }
                 LAUNCH(relax, nblk(rows), BAMG_BLK, s, rows, (const ChainGeo*)lv.dgeo, lv.ncont, (const int*)nvc, KV,
                        lv.B.rp, lv.B.ci, (const T*)lv.B.v, lv.Tm.rp, lv.Tm.ci, (const T*)lv.Tm.v, (const double*)lam,
-                       (const int*)kind, o.omega, (const T*)a, b);
+                       (const int*)kind, o.omega, -1, (const T*)a, b);
                 std::swap(a, b);
             }
             if (a != lv.V) HIPCHK(hipMemcpyAsync(lv.V, a, sizeof(T) * tot, hipMemcpyDeviceToDevice, s));
@@ -1057,6 +1111,7 @@ struct Engine : bamg_ctx {
         allocate(nnzA);
         if (nch > 1) reorder_input(rp, ci, val, nnzA);
         build_b0(rp, ci, val, nnzA);
+        check_colours(0);
         const bool prof = o.profile != 0;
         {
             long long tot = (long long)n * r;
@@ -1111,7 +1166,10 @@ struct Engine : bamg_ctx {
         // algorithmic bytes of one level-0 launch
         const long long n0 = L[0].cont_rows;
         const int vb = sizeof(T);
-        st.sweep_bytes = (long long)(n0 + 1) * 4 + (long long)nnz0 * (4 + vb) + n0 * vb + 2LL * n0 * r * vb;
+        // (one Gauss-Seidel sweep over all colours moves the same data except
+        // D^-1, whose diagonal it takes from the rows)
+        st.sweep_bytes = (long long)(n0 + 1) * 4 + (long long)nnz0 * (4 + vb) + (mcgs ? 0 : n0 * vb) +
+                         2LL * n0 * r * vb;
         if (L.size() > 1) {
             long long nc = L[1].rows;
             st.galerkin_bytes = nc * 9 * (4 + vb) + (long long)(n0 + 1) * 4 + (long long)nnz0 * (4 + vb) +
@@ -1148,7 +1206,18 @@ struct Engine : bamg_ctx {
         T* oth = lv.zero_into_e2 ? lv.e : lv.e2;
         const int nb = nblk(rows);
         const RowMask mk{lv.dgeo, lv.ncont, cmask};     // continuing chains' rows
-        if (o.nu_pre > 0) {
+        auto gs_sweeps = [&](int nu) {
+            for (int k = 0; k < nu; ++k)
+                for (int cc = 0; cc < ncol; ++cc)
+                    LAUNCH((k_mcgs<T, T>), nb, BAMG_BLK, s, rows, (const ChainGeo*)lv.dgeo, lv.ncont, cc, o.gs_omega,
+                           lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const T*)lv.f, cur, mk);
+        };
+        if (mcgs) {
+            // in place from e = 0
+            cur = lv.e;
+            LAUNCH((k_fill_t<T>), nb, BAMG_BLK, s, rows, cur, mk);
+            gs_sweeps(o.nu_pre);
+        } else if (o.nu_pre > 0) {
             LAUNCH((k_jacobi_zero<T, T>), nb, BAMG_BLK, s, rows, (const T*)lv.dinv, (const T*)lv.f, cur, mk);
             for (int k = 1; k < o.nu_pre; ++k) {
                 LAUNCH((k_sweep<T, T>), nb, BAMG_BLK, s, rows, 1, d1, lv.B.rp, lv.B.ci, (const T*)lv.B.v,
@@ -1165,6 +1234,10 @@ struct Engine : bamg_ctx {
                (const T*)lv.r, c.f, (const int*)cmask);
         vcycle(l + 1);
         LAUNCH((k_prolong_add<T, T>), nb, BAMG_BLK, s, rows, lv.pc, (const T*)lv.pv, (const T*)c.e, cur, mk);
+        if (mcgs) {
+            gs_sweeps(o.nu_post);
+            return;
+        }
         for (int k = 0; k < o.nu_post; ++k) {
             LAUNCH((k_sweep<T, T>), nb, BAMG_BLK, s, rows, 1, d1, lv.B.rp, lv.B.ci, (const T*)lv.B.v,
                    (const T*)lv.dinv, (const T*)cur, (const T*)lv.f, oth, mk);
@@ -1556,6 +1629,8 @@ void check_options(const bamg_options& o) {
     if (o.setup_passes < 0 || o.setup_passes > 2) fail(BAMG_EINVAL, "setup_passes must be 1 or 2");
     if (!(o.mlp_judge > 0)) fail(BAMG_EINVAL, "mlp_judge must be positive");
     if (o.precision != BAMG_FP64 && o.precision != BAMG_MIXED) fail(BAMG_EINVAL, "unknown precision %d", o.precision);
+    if (o.relax != BAMG_RELAX_JACOBI && o.relax != BAMG_RELAX_MCGS) fail(BAMG_EINVAL, "unknown relaxation %d", o.relax);
+    if (!(o.gs_omega > 0 && o.gs_omega < 2)) fail(BAMG_EINVAL, "gs_omega must lie in (0, 2)");
 }
 
 bamg_ctx* make_ctx(const bamg_options& o) {
@@ -1632,6 +1707,8 @@ void bamg_options_default(bamg_options* opt) {
     opt->seed = 0;
     opt->setup_passes = 2;
     opt->mlp_judge = 2.0f;
+    opt->relax = BAMG_RELAX_JACOBI;
+    opt->gs_omega = 1.0;
 }
 
 const char* bamg_last_error(void) { return g_last_error.c_str(); }

@@ -124,6 +124,23 @@ __device__ __forceinline__ int find_chain(const ChainGeo* __restrict__ g, int nc
     return lo;
 }
 
+// Colours of the multicolour Gauss-Seidel relaxation: along one grid
+// direction of length m the positions alternate between colours 0 and 1, and
+// a periodic direction of odd length gives its last position colour 2, so
+// neighbours always differ; a point's colour is ca * (colours along b) + cb.
+// Two distinct points within Chebyshev distance 1 (the stencil reach of every
+// operator of the hierarchy) therefore never share a colour.
+__host__ __device__ __forceinline__ int dir_colours(int m, int periodic) {
+    return (periodic && (m & 1) && m > 1) ? 3 : 2;
+}
+__host__ __device__ __forceinline__ int dir_colour(int a, int m, int periodic) {
+    return (periodic && (m & 1) && m > 1 && a == m - 1) ? 2 : (a & 1);
+}
+__device__ __forceinline__ int point_colour(const ChainGeo& g, int li) {
+    const int ia = (int)g.dy.div((uint32_t)li), ib = li - ia * g.ny;
+    return dir_colour(ia, g.nx, g.periodic) * dir_colours(g.ny, g.periodic) + dir_colour(ib, g.ny, g.periodic);
+}
+
 // Chain mask of the batched cycle: a workgroup whose rows [r0, r1] belong only
 // to chains with act[c] == 0 has nothing to do (act == nullptr: every chain is
 // active).  The result is the same for every thread of the workgroup.

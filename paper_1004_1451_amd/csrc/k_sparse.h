@@ -948,18 +948,20 @@ k_galerkin_numeric(int nc, const ChainGeo* __restrict__ geoc, int nch,
 // (lam complex; both columns of a pair form (B - lam T) x, each keeps its own
 // part); D_lam = diag(B) - lam diag(T).  T == identity when trp is null.
 // Column 0 (the null-vector approximation) has lam = 0.  Products are added
-// in CSR order in FP64.
+// in CSR order in FP64.  colour >= 0: one colour of a multicolour
+// Gauss-Seidel sweep (k_mcgs.h), in place (Y == X), other rows untouched.
 template <typename T, typename M, int VP>
 __global__ void __launch_bounds__(BAMG_BLK)
 k_eig_relax(int n, const ChainGeo* __restrict__ geo, int nch, const int* __restrict__ nvc, int KV,
             const int* __restrict__ brp, const int* __restrict__ bci, const M* __restrict__ bv,
             const int* __restrict__ trp, const int* __restrict__ tci, const M* __restrict__ tv,
-            const double* __restrict__ lamall, const int* __restrict__ kindall, double omega,
-            const T* __restrict__ X, T* __restrict__ Y) {
+            const double* __restrict__ lamall, const int* __restrict__ kindall, double omega, int colour,
+            const T* X, T* Y) {
     static_assert(VP % 4 == 0, "row stride must be a multiple of 4");
     const int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
     if (i >= n) return;
     const int ch = find_chain(geo, nch, i);
+    if (colour >= 0 && point_colour(geo[ch], i - geo[ch].off) != colour) return;
     const int nv = nvc[ch];
     auto load = [&](int row, T (&x)[VP]) {
 #pragma unroll
