@@ -159,6 +159,8 @@ def main():
     ap.add_argument("--no-fp64-compare", action="store_true",
                     help="skip the untimed FP64 run that the mixed result is compared with")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--solver", choices=["fgmres", "parnoldi"], default="fgmres",
+                    help="tandem workload: FGMRES (Section 4.2) or preconditioned Arnoldi (Section 4.3)")
     ap.add_argument("--relax", choices=["jacobi", "mcgs"], default="jacobi",
                     help="tandem workload: omega-Jacobi (the paper's) or multicolour Gauss-Seidel sweeps")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -193,7 +195,7 @@ def main():
 
         def step():
             h = B.Hierarchy(ch.n, rp, ci, v, (ch.nx, ch.ny, 0), args.r, opts)
-            info = h.solve(x, args.tol, 200)
+            info = h.solve(x, args.tol, 200, parnoldi=args.solver == "parnoldi")
             st = h.stats()
             h.close()
             return info, st
@@ -227,7 +229,8 @@ def main():
             "dtype": "f64" if prec == B.FP64 else "f32+f64", "data": "synthetic",
             "config": {"workload": f"tandem queue N={args.N} (n={ch.n:,}), rates 11/31,10/31,10/31, r={args.r}, "
                                    f"{args.levels} levels, tol {args.tol:g}", "precision": args.precision,
-                       **({"relax": "multicolour Gauss-Seidel"} if args.relax == "mcgs" else {})},
+                       **({"relax": "multicolour Gauss-Seidel"} if args.relax == "mcgs" else {}),
+                       **({"solver": "preconditioned Arnoldi"} if args.solver == "parnoldi" else {})},
             "roofline": roof, "detail": detail,
         }
         if not args.no_cpu_baseline:

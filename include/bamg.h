@@ -81,6 +81,15 @@ extern "C" {
 #define BAMG_INTERP_MLP 1       /* learned weights with the LS fit as judge      */
 
 #define BAMG_USE_GUESS 1u       /* bamg_solve: start from the caller's x         */
+#define BAMG_PARNOLDI 2u        /* bamg_solve: the multigrid-preconditioned
+                                   Arnoldi method of Section 4.3 instead of
+                                   FGMRES: Arnoldi on C B (C = one cycle) from
+                                   the start vector; after each step the Ritz
+                                   vector of the eigenvalue of H_j closest to 0,
+                                   scaled to sum 1, is the iterate; restarted
+                                   from it every gmres_m steps.  cycles counts
+                                   applications of C; history holds the residual
+                                   after each step.                              */
 
 typedef struct bamg_ctx* bamg_handle;
 

@@ -712,6 +712,84 @@ def fgmres(h: Hierarchy, x: np.ndarray, tol: float, max_cycles: int):
     return x, info
 
 
+# ---------------------------------------------------------------------------
+# Multigrid-preconditioned Arnoldi (Section 4.3): Arnoldi on the operator C B
+# (C = one V-cycle) from the setup's state-vector approximation y; the
+# eigenvalue of H_k = V_k^t (C B) V_k closest to 0 and its eigenvector eta give
+# the Ritz vector V_k eta as the approximation of the state vector.
+# ---------------------------------------------------------------------------
+def parnoldi_basis(h: Hierarchy, y: np.ndarray, k: int):
+    """k Arnoldi steps on C B from y (modified Gram-Schmidt, two passes):
+    returns V (n x (k+1), orthonormal columns) and H ((k+1) x k) with
+    (C B) V[:, :k] = V H."""
+    B = h.levels[0].B
+    V = [y / np.linalg.norm(y)]
+    H = np.zeros((k + 1, k))
+    for j in range(k):
+        w = vcycle(h, B @ V[j])
+        for _ in range(2):
+            for i in range(j + 1):
+                c = np.dot(V[i], w)
+                H[i, j] += c
+                w = w - c * V[i]
+        H[j + 1, j] = np.linalg.norm(w)
+        V.append(w / H[j + 1, j])
+    return np.stack(V, axis=1), H
+
+
+def ritz_nearest_zero(Hk: np.ndarray, Vk: np.ndarray) -> np.ndarray:
+    """The eigenvalue of the square Hk closest to 0 (LAPACK's QR algorithm)
+    and the Ritz vector Vk eta of its eigenvector, scaled to sum 1; the phase
+    of eta makes its largest entry real (a real eigenvalue has a real
+    eigenvector up to that phase)."""
+    theta, S = np.linalg.eig(Hk)
+    i = int(np.argmin(np.abs(theta)))
+    eta = S[:, i]
+    eta = eta * np.exp(-1j * np.angle(eta[np.argmax(np.abs(eta))]))
+    x = Vk @ eta.real
+    return x / np.sum(x)
+
+
+def parnoldi(h: Hierarchy, x: np.ndarray, tol: float, max_cycles: int):
+    """Multigrid-preconditioned Arnoldi (Section 4.3) restarted every m
+    (= gmres_m) steps from the current Ritz vector.  After each step the Ritz
+    vector of the eigenvalue of H_j closest to 0, scaled to sum 1, is the
+    iterate; it stops when ||B x||_1/||x||_1 <= tol (the stopping rule of the
+    GMRES path), at a breakdown, or after max_cycles applications of C."""
+    B = h.levels[0].B
+    m = h.opts.gmres_m
+    info = SolveInfo()
+    x = x / np.sum(x)
+    while True:
+        V = [x / np.linalg.norm(x)]
+        H = np.zeros((m + 1, m))
+        stop = False
+        for j in range(m):
+            w = vcycle(h, B @ V[j])
+            info.cycles += 1
+            for _ in range(2):
+                for i in range(j + 1):
+                    c = np.dot(V[i], w)
+                    H[i, j] += c
+                    w = w - c * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            x = ritz_nearest_zero(H[: j + 1, : j + 1], np.stack(V, axis=1))
+            rel = np.sum(np.abs(B @ x)) / np.sum(np.abs(x))
+            info.residual_l1 = rel
+            info.history.append(rel)
+            if rel <= tol:
+                info.converged = True
+                stop = True
+            if stop or H[j + 1, j] == 0.0 or info.cycles >= max_cycles:
+                stop = stop or info.cycles >= max_cycles
+                break
+            V.append(w / H[j + 1, j])
+        info.restarts += 1
+        if stop:
+            break
+    return x, info
+
+
 def normalise(x: np.ndarray):
     """x >= 0 and sum(x) = 1 (Section 2: the state vector is non-negative);
     returns the vector and the mass removed by the clamp."""
@@ -720,9 +798,12 @@ def normalise(x: np.ndarray):
     return x / np.sum(x), neg
 
 
-def solve(h: Hierarchy, tol: float = 1e-10, max_cycles: int = 200, x: np.ndarray | None = None):
+def solve(h: Hierarchy, tol: float = 1e-10, max_cycles: int = 200, x: np.ndarray | None = None,
+          method: str = "fgmres"):
+    """The state vector from the hierarchy: flexible GMRES (Section 4.2) or
+    the multigrid-preconditioned Arnoldi method (Section 4.3)."""
     x = h.x0.copy() if x is None else x
-    x, info = fgmres(h, x, tol, max_cycles)
+    x, info = (parnoldi if method == "parnoldi" else fgmres)(h, x, tol, max_cycles)
     x, info.clamped_mass = normalise(x)
     B = h.levels[0].B
     info.residual_l1 = np.sum(np.abs(B @ x)) / np.sum(np.abs(x))
@@ -730,8 +811,8 @@ def solve(h: Hierarchy, tol: float = 1e-10, max_cycles: int = 200, x: np.ndarray
 
 
 def stationary(A: sp.csr_matrix, grid: Grid, r: int, opts: Options | None = None,
-               tol: float = 1e-10, max_cycles: int = 200):
+               tol: float = 1e-10, max_cycles: int = 200, method: str = "fgmres"):
     opts = opts or Options()
     h = setup(A, grid, r, opts)
-    x, info = solve(h, tol, max_cycles)
+    x, info = solve(h, tol, max_cycles, method=method)
     return x, info, h

@@ -21,6 +21,7 @@ FP64, MIXED = 0, 1
 INTERP_LS, INTERP_MLP = 0, 1
 RELAX_JACOBI, RELAX_MCGS = 0, 1
 USE_GUESS = 1
+PARNOLDI = 2
 
 X_B_ROWPTR, X_B_COL, X_B_VAL, X_T_ROWPTR, X_T_COL, X_T_VAL = 1, 2, 3, 4, 5, 6
 X_P_COL, X_P_VAL, X_U, X_V, X_LAMBDA, X_VKIND, X_X0, X_W, X_Y, X_U0 = 7, 8, 9, 10, 11, 12, 13, 14, 15, 16
@@ -191,10 +192,10 @@ class Hierarchy:
         rp, ci, v = device_csr(chain)
         return cls(chain.n, rp, ci, v, (chain.nx, chain.ny, chain.periodic), r, options, stream)
 
-    def solve(self, x, tol=1e-10, max_cycles=200, use_guess=False):
+    def solve(self, x, tol=1e-10, max_cycles=200, use_guess=False, parnoldi=False):
         info = SolveInfo()
-        rc = load().bamg_solve(self._h, C.c_void_p(x.data_ptr()), float(tol), int(max_cycles),
-                               USE_GUESS if use_guess else 0, C.byref(info))
+        flags = (USE_GUESS if use_guess else 0) | (PARNOLDI if parnoldi else 0)
+        rc = load().bamg_solve(self._h, C.c_void_p(x.data_ptr()), float(tol), int(max_cycles), flags, C.byref(info))
         _check(rc, allow=(ENOCONV,))
         return info
 
@@ -284,13 +285,14 @@ class BatchedHierarchy(Hierarchy):
                                       C.c_void_p(db.val.data_ptr()), db.grids, int(r), C.byref(opts),
                                       _stream_ptr(stream), C.byref(self._h)))
 
-    def solve_batched(self, x, tol=1e-10, max_cycles=200, use_guess=False):
+    def solve_batched(self, x, tol=1e-10, max_cycles=200, use_guess=False, parnoldi=False):
         """Returns (info, per-chain status int32 array, per-chain residual array)."""
         info = SolveInfo()
         status = np.zeros(self.nchains, dtype=np.int32)
         resid = np.zeros(self.nchains, dtype=np.float64)
+        flags = (USE_GUESS if use_guess else 0) | (PARNOLDI if parnoldi else 0)
         rc = load().bamg_solve_batched(self._h, C.c_void_p(x.data_ptr()), float(tol), int(max_cycles),
-                                       USE_GUESS if use_guess else 0, status.ctypes.data_as(C.c_void_p),
+                                       flags, status.ctypes.data_as(C.c_void_p),
                                        resid.ctypes.data_as(C.c_void_p), C.byref(info))
         _check(rc, allow=(ENOCONV,))
         return info, status, resid
@@ -349,10 +351,10 @@ def relax(row_ptr, col_idx, val, X, R, omega=0.7, nu=1, F=None, stream=None):
                              _stream_ptr(stream)))
 
 
-def stationary(chain, r, tol=1e-10, max_cycles=200, **opts):
+def stationary(chain, r, tol=1e-10, max_cycles=200, parnoldi=False, **opts):
     """Setup + solve for a chain; returns (x as a CPU numpy array, solve info, hierarchy)."""
     import torch
     h = Hierarchy.from_chain(chain, r, default_options(**opts))
     x = torch.empty(chain.n, dtype=torch.float64, device="cuda")
-    info = h.solve(x, tol, max_cycles)
+    info = h.solve(x, tol, max_cycles, parnoldi=parnoldi)
     return x.cpu().numpy(), info, h

@@ -351,6 +351,8 @@ struct Engine : bamg_ctx {
            *ysol = nullptr, *hbuf = nullptr, *rvec = nullptr, *est = nullptr, *xperm = nullptr;
     int *act = nullptr, *kd = nullptr;
     int* cmask = nullptr;            // chains the cycle works on (nch > 1; all ones outside solve)
+    double* hrow = nullptr;          // preconditioned Arnoldi: Hessenberg scratch per chain
+    int* hfail = nullptr;
     double *vin = nullptr, *vout = nullptr;   // permuted vectors of bamg_apply_vcycle
     // graph of one cycle on fixed buffers
     hipGraph_t graph = nullptr;
@@ -1347,6 +1349,109 @@ struct Engine : bamg_ctx {
     // concatenated finest rows; dot products, Hessenberg matrices and the
     // convergence decisions are per chain.  A chain whose inner iteration has
     // stopped is masked until the restart.
+    // Multigrid-preconditioned Arnoldi (Section 4.3) in lockstep over the
+    // chains: Arnoldi on C B from the (normalised) iterate, after each step
+    // the Ritz vector of the eigenvalue of H_j closest to 0, scaled to sum
+    // one, becomes the iterate of every active chain; a chain stops when its
+    // ||B x||_1 / ||x||_1 <= tol or its Krylov space breaks down; the others
+    // restart from their Ritz vector after m steps.
+    void parnoldi_loop(double* xi, double tol, int max_cycles, bamg_solve_info& inf) {
+        const int m = std::max(1, o.gmres_m);
+        const int N = (int)n;
+        const int ld = m + 1, HSg = (m + 1) * m, GS = m + 2;
+        const int nb = nblk(N);
+        const ChainGeo* g0 = L[0].dgeo;
+        if (!hrow) {
+            hrow = A.alloc<double>((size_t)nch * HQR_MAXM * HQR_MAXM);
+            hfail = A.alloc<int>(nch);
+        }
+        std::vector<int> hact(nch, 1), hkd(nch, 0), done(nch, 0);
+        auto residuals = [&](std::vector<double>& rel, std::vector<double>& nu) {
+            LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)xi, -1.0, rvec,
+                   RowMask{g0, nch, nullptr});
+            seg_reduce<RED_ABS>(rvec, nullptr, sc + 1);
+            seg_reduce<RED_ABS>(xi, nullptr, sc + 2);
+            std::vector<double> h = getn(sc, (size_t)nch * SCS);
+            double worst = 0;
+            for (int c = 0; c < nch; ++c) {
+                rel[c] = h[(size_t)c * SCS + 1] / h[(size_t)c * SCS + 2];
+                nu[c] = h[(size_t)c * SCS + 6];
+                worst = std::max(worst, rel[c]);
+            }
+            return worst;
+        };
+        std::vector<double> rel(nch), nu(nch, 1.0);
+        {
+            const double w = residuals(rel, nu);
+            inf.residual_l1 = w;
+            if (inf.history_len < 256) inf.history[inf.history_len++] = w;
+            for (int c = 0; c < nch; ++c) done[c] = rel[c] <= tol;
+        }
+        for (;;) {
+            bool any = false;
+            for (int c = 0; c < nch; ++c) { hact[c] = !done[c]; any |= (bool)hact[c]; }
+            if (!any || inf.cycles >= max_cycles) break;
+            HIPCHK(hipMemcpyAsync(act, hact.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
+            // v_0 = x / ||x||_2
+            seg_reduce<RED_DOT>(xi, xi, sc + 3);
+            LAUNCH(k_seg_scale, nb, BAMG_BLK, s, N, g0, nch, (const int*)nullptr, (const double*)xi,
+                   (const double*)nullptr, (const double*)(sc + 3), SCS, 1, Vk);
+            zero(Hg, sizeof(double) * nch * HSg);
+            for (int j = 0; j < m && inf.cycles < max_cycles; ++j) {
+                // w = C (B v_j)
+                LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v,
+                       (const double*)(Vk + (size_t)j * N), 1.0, rvec, RowMask{g0, nch, act});
+                precondition(rvec, wk);
+                ++inf.cycles;
+                const int P0 = L[0].segp;
+                const dim3 gsg(P0, nch);
+                auto pick = [&](auto k8, auto k16, auto k32, auto k64) {
+                    return j <= 8 ? k8 : j <= 16 ? k16 : j <= 32 ? k32 : k64;
+                };
+                hipLaunchKernelGGL(pick(k_gs_dots<8>, k_gs_dots<16>, k_gs_dots<32>, k_gs_dots<64>), gsg,
+                                   dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, N, j, (const int*)act, (const double*)Vk,
+                                   (const double*)wk, part, GS);
+                hipLaunchKernelGGL(k_gs_final, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0,
+                                   (const int*)act, (const double*)part, GS, hbuf, GS);
+                HIPCHK(hipGetLastError());
+                LAUNCH(k_arn_step, ceil_div(nch, 64), 64, s, nch, j, ld, (const int*)act, (const double*)hbuf2,
+                       (const double*)hbuf, GS, Hg, HSg, gsaux, GS, gscoef, sc + 6, SCS);
+                // Ritz vector of the eigenvalue of H_{j+1} closest to 0
+                LAUNCH(k_hess_near0, nch, BAMG_WAVE, s, j + 1, (const int*)act, (const double*)Hg, HSg, ld, hrow,
+                       ysol, GS, hfail);
+                for (int c = 0; c < nch; ++c) hkd[c] = j + 1;
+                HIPCHK(hipMemcpyAsync(kd, hkd.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
+                LAUNCH(k_seg_ritz, nb, BAMG_BLK, s, N, g0, nch, (const int*)act, (const int*)kd, (const double*)Vk,
+                       (const double*)ysol, GS, xi);
+                // sum one, on the chains that moved only (the others keep their bits)
+                seg_reduce<RED_SUM>(xi, nullptr, sc);
+                LAUNCH(k_seg_scale, nb, BAMG_BLK, s, N, g0, nch, (const int*)act, (const double*)xi,
+                       (const double*)nullptr, (const double*)sc, SCS, 0, xi);
+                const double w = residuals(rel, nu);
+                inf.residual_l1 = w;
+                if (inf.history_len < 256) inf.history[inf.history_len++] = w;
+                bool cont = false;
+                for (int c = 0; c < nch; ++c) {
+                    if (!hact[c]) continue;
+                    if (rel[c] <= tol || !(rel[c] == rel[c])) { done[c] = 1; hact[c] = 0; }
+                    else if (nu[c] == 0.0) hact[c] = 0;     // invariant subspace: restart
+                    cont |= (bool)hact[c];
+                }
+                if (!cont || j + 1 >= m || inf.cycles >= max_cycles) break;
+                HIPCHK(hipMemcpyAsync(act, hact.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
+                hipLaunchKernelGGL(pick(k_gs_update<8>, k_gs_update<16>, k_gs_update<32>, k_gs_update<64>), gsg,
+                                   dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, N, j, (const int*)act, Vk, (const double*)wk,
+                                   (const double*)gscoef, part, GS);
+                hipLaunchKernelGGL(k_gs_final, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0,
+                                   (const int*)act, (const double*)part, GS, hbuf2, GS);
+                HIPCHK(hipGetLastError());
+            }
+            ++inf.restarts;
+            for (int c = 0; c < nch; ++c)
+                if (!(rel[c] == rel[c])) fail(BAMG_EDEVICE, "preconditioned Arnoldi: non-finite residual (chain %d)", c);
+        }
+    }
+
     int solve(double* x, double tol, int max_cycles, uint32_t flags, int32_t* status, double* resid,
               bamg_solve_info* info) override {
         auto t0 = std::chrono::steady_clock::now();
@@ -1393,95 +1498,99 @@ struct Engine : bamg_ctx {
         const int nb = nblk(N);
         std::vector<int> conv(nch, 0), hact(nch), hkd(nch);
         std::vector<double> rel(nch, 0.0);
-        for (;;) {
-            // r = -B x; per-chain relative 1-norm residual
-            LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)xi, -1.0, rvec,
-                   RowMask{g0, nch, nullptr});
-            seg_reduce<RED_ABS>(rvec, nullptr, sc + 1);
-            seg_reduce<RED_ABS>(xi, nullptr, sc + 2);
-            seg_reduce<RED_DOT>(rvec, rvec, sc + 3);
-            std::vector<double> h = getn(sc, (size_t)nch * SCS);
-            bool all = true, nan = false;
-            double worst = 0;
-            for (int c = 0; c < nch; ++c) {
-                rel[c] = h[(size_t)c * SCS + 1] / h[(size_t)c * SCS + 2];
-                conv[c] = rel[c] <= tol;
-                all &= (bool)conv[c];
-                nan |= !(rel[c] == rel[c]);
-                worst = std::max(worst, rel[c]);
-            }
-            inf.residual_l1 = worst;
-            if (inf.history_len < 256) inf.history[inf.history_len++] = worst;
-            if (all || inf.cycles >= max_cycles || nan) break;
-            // inner iteration for the unconverged chains
-            std::vector<double> itol(nch);
-            for (int c = 0; c < nch; ++c) {
-                double r1 = h[(size_t)c * SCS + 1], x1 = h[(size_t)c * SCS + 2], b2 = h[(size_t)c * SCS + 3];
-                itol[c] = 0.5 * tol * x1 * std::sqrt(b2) / r1;
-                hact[c] = conv[c] ? 0 : 1;
-                hkd[c] = 0;
-            }
-            HIPCHK(hipMemcpyAsync(act, hact.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
-            zero(Hg, sizeof(double) * nch * HSg);
-            LAUNCH(k_seg_gmres_init, nch, 64, s, nch, m, (const double*)(sc + 3), SCS, g, GS);
-            LAUNCH(k_seg_scale, nb, BAMG_BLK, s, N, g0, nch, (const int*)nullptr, (const double*)rvec,
-                   (const double*)nullptr, (const double*)(sc + 3), SCS, 1, Vk);
-            for (int j = 0; j < m && inf.cycles < max_cycles; ++j) {
-                double* vj = Vk + (size_t)j * N;
-                double* zj = Zk + (size_t)j * N;
-                // once most chains have stopped, the masked cycle is little
-                // work in many launches: replay it from a graph instead
-                if (nch > 1 && o.cycle_mode == 0 && cycle_decided && !use_graph) {
-                    long long act_rows = 0;
-                    for (int c = 0; c < nch; ++c) act_rows += hact[c] ? chains[c].n : 0;
-                    if (4 * act_rows < n) { use_graph = true; st.cycle_graph = 1; }
-                }
-                precondition(vj, zj);
-                ++inf.cycles;
-                LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)zj, 1.0, wk,
-                       RowMask{g0, nch, cmask});
-                // Gram-Schmidt with the delayed second pass: dots of w, the
-                // per-chain step (finish v_j, correct column j-1, column j,
-                // Givens), and, for chains that go on, the update pass that
-                // finishes q_j and makes v_{j+1} with its dots
-                const int P0 = L[0].segp;
-                const dim3 gsg(P0, nch);
-                auto pick = [&](auto k8, auto k16, auto k32, auto k64) {
-                    return j <= 8 ? k8 : j <= 16 ? k16 : j <= 32 ? k32 : k64;
-                };
-                hipLaunchKernelGGL(pick(k_gs_dots<8>, k_gs_dots<16>, k_gs_dots<32>, k_gs_dots<64>), gsg, dim3(BAMG_BLK),
-                                   0, s, g0, SEG_ROWS, N, j, (const int*)act, (const double*)Vk, (const double*)wk,
-                                   part, GS);
-                hipLaunchKernelGGL(k_gs_final, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0,
-                                   (const int*)act, (const double*)part, GS, hbuf, GS);
-                HIPCHK(hipGetLastError());
-                LAUNCH(k_gs_step, ceil_div(nch, 64), 64, s, nch, j, ld, (const int*)act, (const double*)hbuf2,
-                       (const double*)hbuf, GS, Hg, HSg, cs, sn, g, gsaux, GS, gscoef, est);
-                // |g_{j+1}| = 0 also covers a breakdown (||w|| = 0 gives s_j = 0)
-                std::vector<double> e = getn(est, nch);
-                bool any = false;
+        if (flags & BAMG_PARNOLDI) {
+            parnoldi_loop(xi, tol, max_cycles, inf);
+        } else {
+            for (;;) {
+                // r = -B x; per-chain relative 1-norm residual
+                LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)xi, -1.0, rvec,
+                       RowMask{g0, nch, nullptr});
+                seg_reduce<RED_ABS>(rvec, nullptr, sc + 1);
+                seg_reduce<RED_ABS>(xi, nullptr, sc + 2);
+                seg_reduce<RED_DOT>(rvec, rvec, sc + 3);
+                std::vector<double> h = getn(sc, (size_t)nch * SCS);
+                bool all = true, nan = false;
+                double worst = 0;
                 for (int c = 0; c < nch; ++c) {
-                    if (!hact[c]) continue;
-                    hkd[c] = j + 1;
-                    if (e[c] <= itol[c] || e[c] == 0.0) hact[c] = 0;
-                    any |= (bool)hact[c];
+                    rel[c] = h[(size_t)c * SCS + 1] / h[(size_t)c * SCS + 2];
+                    conv[c] = rel[c] <= tol;
+                    all &= (bool)conv[c];
+                    nan |= !(rel[c] == rel[c]);
+                    worst = std::max(worst, rel[c]);
                 }
-                if (!any || j + 1 >= m || inf.cycles >= max_cycles) break;
+                inf.residual_l1 = worst;
+                if (inf.history_len < 256) inf.history[inf.history_len++] = worst;
+                if (all || inf.cycles >= max_cycles || nan) break;
+                // inner iteration for the unconverged chains
+                std::vector<double> itol(nch);
+                for (int c = 0; c < nch; ++c) {
+                    double r1 = h[(size_t)c * SCS + 1], x1 = h[(size_t)c * SCS + 2], b2 = h[(size_t)c * SCS + 3];
+                    itol[c] = 0.5 * tol * x1 * std::sqrt(b2) / r1;
+                    hact[c] = conv[c] ? 0 : 1;
+                    hkd[c] = 0;
+                }
                 HIPCHK(hipMemcpyAsync(act, hact.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
-                hipLaunchKernelGGL(pick(k_gs_update<8>, k_gs_update<16>, k_gs_update<32>, k_gs_update<64>), gsg,
-                                   dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, N, j, (const int*)act, Vk, (const double*)wk,
-                                   (const double*)gscoef, part, GS);
-                hipLaunchKernelGGL(k_gs_final, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0,
-                                   (const int*)act, (const double*)part, GS, hbuf2, GS);
-                HIPCHK(hipGetLastError());
+                zero(Hg, sizeof(double) * nch * HSg);
+                LAUNCH(k_seg_gmres_init, nch, 64, s, nch, m, (const double*)(sc + 3), SCS, g, GS);
+                LAUNCH(k_seg_scale, nb, BAMG_BLK, s, N, g0, nch, (const int*)nullptr, (const double*)rvec,
+                       (const double*)nullptr, (const double*)(sc + 3), SCS, 1, Vk);
+                for (int j = 0; j < m && inf.cycles < max_cycles; ++j) {
+                    double* vj = Vk + (size_t)j * N;
+                    double* zj = Zk + (size_t)j * N;
+                    // once most chains have stopped, the masked cycle is little
+                    // work in many launches: replay it from a graph instead
+                    if (nch > 1 && o.cycle_mode == 0 && cycle_decided && !use_graph) {
+                        long long act_rows = 0;
+                        for (int c = 0; c < nch; ++c) act_rows += hact[c] ? chains[c].n : 0;
+                        if (4 * act_rows < n) { use_graph = true; st.cycle_graph = 1; }
+                    }
+                    precondition(vj, zj);
+                    ++inf.cycles;
+                    LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)zj, 1.0, wk,
+                           RowMask{g0, nch, cmask});
+                    // Gram-Schmidt with the delayed second pass: dots of w, the
+                    // per-chain step (finish v_j, correct column j-1, column j,
+                    // Givens), and, for chains that go on, the update pass that
+                    // finishes q_j and makes v_{j+1} with its dots
+                    const int P0 = L[0].segp;
+                    const dim3 gsg(P0, nch);
+                    auto pick = [&](auto k8, auto k16, auto k32, auto k64) {
+                        return j <= 8 ? k8 : j <= 16 ? k16 : j <= 32 ? k32 : k64;
+                    };
+                    hipLaunchKernelGGL(pick(k_gs_dots<8>, k_gs_dots<16>, k_gs_dots<32>, k_gs_dots<64>), gsg, dim3(BAMG_BLK),
+                                       0, s, g0, SEG_ROWS, N, j, (const int*)act, (const double*)Vk, (const double*)wk,
+                                       part, GS);
+                    hipLaunchKernelGGL(k_gs_final, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0,
+                                       (const int*)act, (const double*)part, GS, hbuf, GS);
+                    HIPCHK(hipGetLastError());
+                    LAUNCH(k_gs_step, ceil_div(nch, 64), 64, s, nch, j, ld, (const int*)act, (const double*)hbuf2,
+                           (const double*)hbuf, GS, Hg, HSg, cs, sn, g, gsaux, GS, gscoef, est);
+                    // |g_{j+1}| = 0 also covers a breakdown (||w|| = 0 gives s_j = 0)
+                    std::vector<double> e = getn(est, nch);
+                    bool any = false;
+                    for (int c = 0; c < nch; ++c) {
+                        if (!hact[c]) continue;
+                        hkd[c] = j + 1;
+                        if (e[c] <= itol[c] || e[c] == 0.0) hact[c] = 0;
+                        any |= (bool)hact[c];
+                    }
+                    if (!any || j + 1 >= m || inf.cycles >= max_cycles) break;
+                    HIPCHK(hipMemcpyAsync(act, hact.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
+                    hipLaunchKernelGGL(pick(k_gs_update<8>, k_gs_update<16>, k_gs_update<32>, k_gs_update<64>), gsg,
+                                       dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, N, j, (const int*)act, Vk, (const double*)wk,
+                                       (const double*)gscoef, part, GS);
+                    hipLaunchKernelGGL(k_gs_final, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0,
+                                       (const int*)act, (const double*)part, GS, hbuf2, GS);
+                    HIPCHK(hipGetLastError());
+                }
+                HIPCHK(hipMemcpyAsync(kd, hkd.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
+                LAUNCH(k_seg_gmres_y, ceil_div(nch, 64), 64, s, nch, ld, (const int*)kd, (const double*)Hg, HSg,
+                       (const double*)g, GS, ysol);
+                LAUNCH(k_seg_xupdate, nb, BAMG_BLK, s, N, g0, nch, (const int*)kd, (const double*)Zk, (const double*)ysol,
+                       GS, xi);
+                normalise();
+                ++inf.restarts;
             }
-            HIPCHK(hipMemcpyAsync(kd, hkd.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
-            LAUNCH(k_seg_gmres_y, ceil_div(nch, 64), 64, s, nch, ld, (const int*)kd, (const double*)Hg, HSg,
-                   (const double*)g, GS, ysol);
-            LAUNCH(k_seg_xupdate, nb, BAMG_BLK, s, N, g0, nch, (const int*)kd, (const double*)Zk, (const double*)ysol,
-                   GS, xi);
-            normalise();
-            ++inf.restarts;
         }
         // x >= 0, sum 1 per chain
         seg_reduce<RED_NEGSUM>(xi, nullptr, sc + 5);
@@ -1735,6 +1844,7 @@ int bamg_solve(bamg_handle h, double* x, double tol, int32_t max_cycles, uint32_
     int rc = run_guarded([&] {
         if (!h || !x) fail(BAMG_EINVAL, "NULL handle or x");
         if (!(tol > 0) || max_cycles < 0) fail(BAMG_EINVAL, "invalid tol or max_cycles");
+        if (flags & ~(BAMG_USE_GUESS | BAMG_PARNOLDI)) fail(BAMG_EINVAL, "unknown solve flags 0x%x", flags);
         code = h->solve(x, tol, max_cycles, flags, nullptr, nullptr, info);
     });
     if (rc != BAMG_OK) return rc;
@@ -1748,6 +1858,7 @@ int bamg_solve_batched(bamg_handle h, double* x, double tol, int32_t max_cycles,
     int rc = run_guarded([&] {
         if (!h || !x) fail(BAMG_EINVAL, "NULL handle or x");
         if (!(tol > 0) || max_cycles < 0) fail(BAMG_EINVAL, "invalid tol or max_cycles");
+        if (flags & ~(BAMG_USE_GUESS | BAMG_PARNOLDI)) fail(BAMG_EINVAL, "unknown solve flags 0x%x", flags);
         code = h->solve(x, tol, max_cycles, flags, chain_status, chain_residual, info);
     });
     if (rc != BAMG_OK) return rc;

@@ -913,6 +913,17 @@ __global__ void k_cz_tables(int nch, const int* __restrict__ nsel, int NS, const
     nentc[ch] = ne + 1;
 }
 
+// One wavefront per chain with act[c]: the nearest-to-zero eigenvector of
+// the leading k x k block of its Arnoldi matrix (hessenberg_near_zero_body).
+__global__ void __launch_bounds__(BAMG_WAVE)
+k_hess_near0(int k, const int* __restrict__ act, const double* __restrict__ Hall, int HS, int ld,
+             double* __restrict__ Hrow, double* __restrict__ eta, int ES, int* __restrict__ fail) {
+    const int c = blockIdx.x;
+    if (!act[c]) return;
+    hessenberg_near_zero_body(k, Hall + (size_t)c * HS, ld, Hrow + (size_t)c * HQR_MAXM * HQR_MAXM,
+                              eta + (size_t)c * ES, fail + c);
+}
+
 // One wavefront per chain: eigenvalues of its Arnoldi Hessenberg matrix
 // (stride HS), selection and eigenvectors (see hessenberg_eig_body).
 // Chains without eigenpairs report no selection.

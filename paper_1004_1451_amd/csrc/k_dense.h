@@ -840,6 +840,63 @@ __device__ void hessenberg_eig_body(int m, int want, const double* __restrict__ 
     if (lane == 0) { nsel_out[0] = ne; nsel_out[1] = ncols; nsel_out[2] = fail; }
 }
 
+// One wavefront: the eigenvalue of the leading k x k block of a Hessenberg
+// matrix H (column-major, leading dimension ld) closest to 0 and its
+// eigenvector by three steps of inverse iteration with (H - theta I),
+// normalised to ||eta||_2 = 1 with its largest-modulus entry (lowest index on
+// ties) real and positive; the real part goes to eta[0..k-1].  Hrow: scratch
+// of k * k doubles (row-major copy).  *fail = 1 when the QR iteration fails.
+__device__ void hessenberg_near_zero_body(int k, const double* __restrict__ Hh, int ld, double* __restrict__ Hrow,
+                                          double* __restrict__ eta, int* __restrict__ fail_out) {
+    __shared__ double A[HQR_MAXM * HQR_LD];
+    __shared__ double wr[HQR_MAXM], wi[HQR_MAXM], zr[HQR_MAXM], zi[HQR_MAXM];
+    __shared__ int fail;
+    const int lane = threadIdx.x;
+    if (lane == 0) fail = 0;
+    double hn = 0;
+    for (int i = 0; i < k; ++i) {
+        double v = 0;
+        if (lane < k) v = (i <= lane + 1) ? Hh[(size_t)lane * ld + i] : 0.0;
+        if (lane < k) { A[i * HQR_LD + lane] = v; Hrow[(size_t)i * k + lane] = v; }
+        hn = fmax(hn, fabs(v));
+    }
+#pragma unroll
+    for (int off = BAMG_WAVE / 2; off > 0; off >>= 1) hn = fmax(hn, __shfl_xor(hn, off, BAMG_WAVE));
+    __threadfence_block();
+    lds_sync();
+    hqr_wave(k, A, wr, wi, &fail);
+    lds_sync();
+    int best = 0;
+    double bm = wr[0] * wr[0] + wi[0] * wi[0];
+    for (int i = 1; i < k; ++i) {
+        const double mod = wr[i] * wr[i] + wi[i] * wi[i];
+        if (mod < bm) { bm = mod; best = i; }
+    }
+    const double thr = wr[best], thi = wi[best];
+    if (lane < k) { zr[lane] = 1.0; zi[lane] = 0.0; }
+    lds_sync();
+    for (int itn = 0; itn < 3; ++itn) {
+        hess_shift_solve_wave(k, Hrow, thr, thi, A, zr, zi, hn);
+        double s = lane < k ? zr[lane] * zr[lane] + zi[lane] * zi[lane] : 0.0;
+        s = wave_sum(s);
+        s = __shfl(s, 0, BAMG_WAVE);
+        const double nr = sqrt(s);
+        lds_sync();
+        if (lane < k) { zr[lane] /= nr; zi[lane] /= nr; }
+        lds_sync();
+    }
+    // phase: the largest-modulus entry real and positive
+    double bmod = -1;
+    int bi = 0;
+    for (int i = 0; i < k; ++i) {
+        const double m2 = zr[i] * zr[i] + zi[i] * zi[i];
+        if (m2 > bmod) { bmod = m2; bi = i; }
+    }
+    const double mr = zr[bi], mi = zi[bi], md = sqrt(mr * mr + mi * mi);
+    if (lane < k) eta[lane] = (zr[lane] * mr + zi[lane] * mi) / md;
+    if (lane == 0) *fail_out = fail;
+}
+
 // Ritz vector of entry e: v = Vb[:, 0:m] s_e (complex), into out_re / out_im.
 __global__ void k_ritz(int n, int m, const double* __restrict__ Vb, const double* __restrict__ s,
                        double* __restrict__ out_re, double* __restrict__ out_im) {

@@ -495,6 +495,70 @@ __global__ void k_gs_step(int nch, int j, int ld, const int* __restrict__ act, c
     cf[2 * GS_MAXB + 2] = nuj > 0.0 ? 1.0 / nuj : 0.0;
 }
 
+// The same step for the multigrid-preconditioned Arnoldi method (Section
+// 4.3): H is kept as it is (no Givens rotations) because its eigenpairs are
+// wanted.  Column j-1 becomes h + nu_{j-1} a with subdiagonal nu_{j-1} alpha,
+// column j is (d_b, h_j, nu_j); the update pass's coefficients as in
+// k_gs_step; sc[c * SS] = nu_j (0 at a breakdown).
+__global__ void k_arn_step(int nch, int j, int ld, const int* __restrict__ act, const double* __restrict__ dvall,
+                           const double* __restrict__ dwall, int DS, double* __restrict__ Hall, int HS,
+                           double* __restrict__ auxall, int GS, double* __restrict__ coefall,
+                           double* __restrict__ sc, int SS) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nch || !act[c]) return;
+    const double* a = dvall + (size_t)c * DS;
+    const double* d = dwall + (size_t)c * DS;
+    double* H = Hall + (size_t)c * HS;
+    double* nu = auxall + (size_t)c * 3 * GS;
+    double* cf = coefall + (size_t)c * GS_CS;
+    double alpha = 1.0, hj, ad = 0.0;
+    bool broke = false;
+    if (j > 0) {
+        double s2 = 0.0;
+        for (int b = 0; b < j; ++b) { s2 += a[b] * a[b]; ad += a[b] * d[b]; }
+        const double al2 = a[j] - s2;
+        alpha = al2 > 0.0 ? sqrt(al2) : 0.0;
+        broke = !(alpha > 0.0);
+        double* cp = H + (size_t)(j - 1) * ld;
+        const double np = nu[j - 1];
+        for (int b = 0; b < j; ++b) cp[b] += np * a[b];
+        cp[j] = np * alpha;
+        hj = broke ? 0.0 : (d[j] - ad) / alpha;
+    } else {
+        hj = d[0];
+    }
+    double* col = H + (size_t)j * ld;
+    double nu2 = d[j + 1] - hj * hj;
+    for (int b = 0; b < j; ++b) {
+        col[b] = broke ? 0.0 : d[b];
+        nu2 -= d[b] * d[b];
+    }
+    col[j] = hj;
+    const double nuj = (!broke && nu2 > 0.0) ? sqrt(nu2) : 0.0;
+    col[j + 1] = nuj;
+    nu[j] = nuj;
+    sc[(size_t)c * SS] = nuj;
+    for (int b = 0; b < j; ++b) { cf[b] = a[b]; cf[GS_MAXB + b] = d[b]; }
+    cf[2 * GS_MAXB] = 1.0 / alpha;
+    cf[2 * GS_MAXB + 1] = hj;
+    cf[2 * GS_MAXB + 2] = nuj > 0.0 ? 1.0 / nuj : 0.0;
+}
+
+// x_i = sum_{b < kd[c]} eta_b V_b[i] on the rows of chains with act[c].
+__global__ void k_seg_ritz(int N, const ChainGeo* __restrict__ geo, int nch, const int* __restrict__ act,
+                           const int* __restrict__ kd, const double* __restrict__ V, const double* __restrict__ etaall,
+                           int ES, double* __restrict__ x) {
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (i >= N) return;
+    const int c = find_chain(geo, nch, i);
+    if (!act[c]) return;
+    const int k = kd[c];
+    const double* eta = etaall + (size_t)c * ES;
+    double s = 0.0;
+    for (int b = 0; b < k; ++b) s += eta[b] * V[(size_t)b * N + i];
+    x[i] = s;
+}
+
 // g = [beta_c, 0, ...] for every chain (beta2 per chain at stride).
 __global__ void k_seg_gmres_init(int nch, int m, const double* __restrict__ beta2, int stride, double* __restrict__ gall,
                                  int GS) {
