@@ -305,8 +305,12 @@ def ls_fit(X: np.ndarray, w: np.ndarray, g: Grid, caliber: int):
             Gjg = Gi[:, :, s_]
             piv = Gi[:, s_, s_] - np.einsum("pa,pa->p", Gjg * Ji, _masked_solve(Gi, Gjg, Ji))
             adm = piv > PIVOT_RTOL * Gi[:, s_, s_]
+            # the functional only for admissible candidates (an inadmissible
+            # one may make G_SS exactly singular)
             S = Ji.copy(); S[:, s_] = True
-            L = sigma[ix] - np.einsum("pa,pa->p", bi * S, _masked_solve(Gi, bi, S))
+            L = np.full(len(ix), np.inf)
+            if np.any(adm):
+                L[adm] = sigma[ix[adm]] - np.einsum("pa,pa->p", bi[adm] * S[adm], _masked_solve(Gi[adm], bi[adm], S[adm]))
             better = adm & (L < best_L[ix])
             best_L[ix] = np.where(better, L, best_L[ix])
             best_g[ix] = np.where(better, s_, best_g[ix])
@@ -541,6 +545,7 @@ class Options:
     gmres_m: int = 50
     seed: int = 0
     coarse_max: int = 1024
+    mu: int = 1                # cycle index of Algorithm 3: 1 = V, 2 = W
     relax: str = "jacobi"      # or "mcgs": multicolour Gauss-Seidel
     gs_omega: float = 1.0      # weight of the Gauss-Seidel update
 
@@ -579,42 +584,56 @@ def build_level(lv: Level, X: np.ndarray, opts: Options):
     return P, Q, J, Bc, Tc
 
 
-def setup(A: sp.csr_matrix, grid: Grid, r: int, opts: Options) -> Hierarchy:
-    n = A.shape[0]
-    plan = level_plan(grid, opts.levels, opts.coarse_max)
-    B0 = b_from_a(A.tocsr())
-    T0 = sp.identity(n, format="csr")
-    levels = [Level(plan[0], B0, T0)]
-    U = initial_tvs(n, r, opts.seed)
-    # down-leg: relax U_l, fit P_l to U_l, Galerkin products, inject U
-    for l in range(len(plan) - 1):
-        lv = levels[l]
-        if opts.relax == "mcgs":
-            check_colouring(lv.B, colours(lv.grid)[0])
-        U = relax(lv, U, opts, opts.nu_setup)
-        lv.U = U
-        P, Q, J, Bc, Tc = build_level(lv, U, opts)
+def mle_cycle(levels: list, l: int, plan: list, opts: Options, use_v: bool):
+    """Algorithm 3 (bootamg_mle) from level l.  levels[l] holds B_l, T_l and
+    U_l (and V_l from an earlier cycle when use_v).  Relax U_l; then mu times:
+    fit P_l to U_l (joined by V_l after the first round, or from the start
+    when use_v), Q_l, B_{l+1}, T_{l+1}, inject U_{l+1} = R U_l, recurse, and
+    bring the coarse eigenvector approximations up: V_l = P_l V_{l+1},
+    relaxed on (B_l - lam T_l) v = 0 with lam updated.  The coarsest level
+    solves its eigenproblem.  Returns the eigenvalue entries."""
+    lv = levels[l]
+    if l == len(plan) - 1:
+        _, entries, V = coarsest_eigs(lv.B.toarray(), lv.T.toarray(), opts.n_eig)
+        lv.V = V
+        return entries
+    if opts.relax == "mcgs":
+        check_colouring(lv.B, colours(lv.grid)[0])
+    lv.U = relax(lv, lv.U, opts, opts.nu_setup)
+    entries = None
+    for m in range(opts.mu):
+        X = np.concatenate([lv.U, lv.V], axis=1) if (use_v or m > 0) else lv.U
+        P, Q, J, Bc, Tc = build_level(lv, X, opts)
         lv.P, lv.Q, lv.J = P, Q, J
-        levels.append(Level(plan[l + 1], Bc, Tc))
-        U = inject(U, lv.grid)
-    first = [(lv.P, lv.B, lv.T) for lv in levels]
-    # coarsest: exact eigensolve
-    cl = levels[-1]
-    cl.U = U
-    Bd, Td = cl.B.toarray(), cl.T.toarray()
-    y, entries, V = coarsest_eigs(Bd, Td, opts.n_eig)
-    cl.V = V
-    # up-leg: interpolate, relax, update the eigenvalue approximations
-    for l in range(len(plan) - 2, -1, -1):
-        lv = levels[l]
-        V = lv.P @ V
+        if len(levels) == l + 1:
+            levels.append(Level(plan[l + 1], Bc, Tc))
+        else:
+            levels[l + 1].B, levels[l + 1].T = Bc, Tc
+        levels[l + 1].U = inject(lv.U, lv.grid)
+        entries = mle_cycle(levels, l + 1, plan, opts, use_v)
         gs = None
         if opts.relax == "mcgs":
             col, ncol = colours(lv.grid)
             check_colouring(lv.T, col)
             gs = (col, ncol, opts.gs_omega)
-        V, entries = eig_relax(lv.B, lv.T, V, entries, opts.omega, opts.nu_setup, gs)
-        lv.V = V
+        lv.V, entries = eig_relax(lv.B, lv.T, lv.P @ levels[l + 1].V, entries, opts.omega, opts.nu_setup, gs)
+    return entries
+
+
+def _first_level(A: sp.csr_matrix, grid: Grid, r: int, opts: Options):
+    plan = level_plan(grid, opts.levels, opts.coarse_max)
+    n = A.shape[0]
+    lv = Level(plan[0], b_from_a(A.tocsr()), sp.identity(n, format="csr"))
+    lv.U = initial_tvs(n, r, opts.seed)
+    return plan, [lv]
+
+
+def setup(A: sp.csr_matrix, grid: Grid, r: int, opts: Options) -> Hierarchy:
+    """The setup of Section 1: one MLE cycle (Algorithm 3 with opts.mu) from
+    the random test vectors, then every P, B, T recomputed from U u V."""
+    plan, levels = _first_level(A, grid, r, opts)
+    entries = mle_cycle(levels, 0, plan, opts, use_v=False)
+    first = [(lv.P, lv.B, lv.T) for lv in levels]
     x0 = levels[0].V[:, 0] / np.sum(levels[0].V[:, 0])
     # recompute every P, B, T from the enriched sets U u V
     for l in range(len(plan) - 1):
@@ -630,6 +649,33 @@ def setup(A: sp.csr_matrix, grid: Grid, r: int, opts: Options) -> Hierarchy:
     Bd = cl.B.toarray()
     svd = coarsest_svd(Bd)
     return Hierarchy(levels, opts, coarsest_pinv(Bd, svd), coarsest_null(Bd, cl.T.toarray(), svd), entries, x0, first)
+
+
+def mle_iteration(A: sp.csr_matrix, grid: Grid, r: int, opts: Options | None = None, tol: float = 1e-8,
+                  max_cycles: int = 50):
+    """The MLE iteration as a stand-alone solver (Section 4.1): setup cycles
+    (Algorithm 3 with opts.mu) repeated, the first from the random test
+    vectors and each later one fitting P_l to U_l u V_l of the previous cycle
+    on every level (the enriched test sets of Section 1); after each cycle
+    x = V_0[:, 0] / sum is the iterate, until ||B x||_1 / ||x||_1 <= tol.
+    Returns (x, info with cycles = MLE cycles, levels)."""
+    opts = opts or Options()
+    plan, levels = _first_level(A, grid, r, opts)
+    B = levels[0].B
+    info = SolveInfo()
+    x = None
+    for k in range(max_cycles):
+        mle_cycle(levels, 0, plan, opts, use_v=k > 0)
+        info.cycles += 1
+        v = levels[0].V[:, 0]
+        x = v / np.sum(v)
+        rel = np.sum(np.abs(B @ x)) / np.sum(np.abs(x))
+        info.residual_l1 = rel
+        info.history.append(rel)
+        if rel <= tol:
+            info.converged = True
+            break
+    return x, info, levels
 
 
 # ---------------------------------------------------------------------------
