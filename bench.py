@@ -159,8 +159,10 @@ def main():
     ap.add_argument("--no-fp64-compare", action="store_true",
                     help="skip the untimed FP64 run that the mixed result is compared with")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--solver", choices=["fgmres", "parnoldi"], default="fgmres",
-                    help="tandem workload: FGMRES (Section 4.2) or preconditioned Arnoldi (Section 4.3)")
+    ap.add_argument("--solver", choices=["fgmres", "parnoldi", "mle"], default="fgmres",
+                    help="tandem workload: FGMRES (Section 4.2), preconditioned Arnoldi (Section 4.3) or the "
+                         "stand-alone MLE iteration (Section 4.1)")
+    ap.add_argument("--mu", type=int, choices=[1, 2], default=1, help="setup cycle index (1 = V, 2 = W)")
     ap.add_argument("--relax", choices=["jacobi", "mcgs"], default="jacobi",
                     help="tandem workload: omega-Jacobi (the paper's) or multicolour Gauss-Seidel sweeps")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -191,11 +193,14 @@ def main():
         rp, ci, v = B.device_csr(ch)
         x = torch.empty(ch.n, dtype=torch.float64, device="cuda")
         relax = B.RELAX_MCGS if args.relax == "mcgs" else B.RELAX_JACOBI
-        opts = B.default_options(levels=args.levels, precision=prec, profile=1, relax=relax)
+        opts = B.default_options(levels=args.levels, precision=prec, profile=1, relax=relax, mu=args.mu)
 
         def step():
             h = B.Hierarchy(ch.n, rp, ci, v, (ch.nx, ch.ny, 0), args.r, opts)
-            info = h.solve(x, args.tol, 200, parnoldi=args.solver == "parnoldi")
+            if args.solver == "mle":
+                info = h.mle_iterate(x, args.tol, 200)
+            else:
+                info = h.solve(x, args.tol, 200, parnoldi=args.solver == "parnoldi")
             st = h.stats()
             h.close()
             return info, st
@@ -217,7 +222,7 @@ def main():
             # outside the timed region: the plain FP64 form, its time per step
             # and how far the mixed solution is from it
             x_mixed = x.clone()
-            opts = B.default_options(levels=args.levels, precision=B.FP64, profile=1, relax=relax)
+            opts = B.default_options(levels=args.levels, precision=B.FP64, profile=1, relax=relax, mu=args.mu)
             sec64, res64 = _timed(step, argparse.Namespace(warmup=1, steps=max(1, min(args.steps, 3))))
             detail["fp64_ms_per_step"] = round(sec64 * 1e3, 3)
             detail["fp64_cycles"] = res64[-1][0].cycles
@@ -230,7 +235,9 @@ def main():
             "config": {"workload": f"tandem queue N={args.N} (n={ch.n:,}), rates 11/31,10/31,10/31, r={args.r}, "
                                    f"{args.levels} levels, tol {args.tol:g}", "precision": args.precision,
                        **({"relax": "multicolour Gauss-Seidel"} if args.relax == "mcgs" else {}),
-                       **({"solver": "preconditioned Arnoldi"} if args.solver == "parnoldi" else {})},
+                       **({"solver": {"parnoldi": "preconditioned Arnoldi", "mle": "MLE iteration"}[args.solver]}
+                          if args.solver != "fgmres" else {}),
+                       **({"setup_cycle": "W"} if args.mu == 2 else {})},
             "roofline": roof, "detail": detail,
         }
         if not args.no_cpu_baseline:

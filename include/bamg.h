@@ -135,6 +135,10 @@ typedef struct {
                             BAMG_RELAX_MCGS (multicolour Gauss-Seidel) for the
                             test-vector, eigenvector and cycle sweeps         */
     double gs_omega;     /* weight of the Gauss-Seidel update (default 1)     */
+    int32_t mu;          /* cycle index of the setup cycle (Algorithm 3): 1 =
+                            V-cycle (default), 2 = W-cycle (every level fits,
+                            recurses and brings the eigenvectors up twice, the
+                            second time fitting to U and V)                   */
 } bamg_options;
 
 typedef struct {
@@ -209,7 +213,7 @@ typedef struct {
 /* Fill *opt with the defaults: levels 0, coarse_max 1024, nu_setup 4,
    V(2,2), omega 0.7, caliber 4, n_eig 6, arnoldi_m 40, gmres_m 50,
    FP64, LS interpolation, seed 0, no budget, no profiling, 2 setup passes,
-   mlp_judge 2, omega-Jacobi relaxation (gs_omega 1). */
+   mlp_judge 2, omega-Jacobi relaxation (gs_omega 1), mu 1. */
 void bamg_options_default(bamg_options* opt);
 
 /* Build the hierarchy for A (device CSR, see conventions) with r initial test
@@ -261,6 +265,19 @@ int bamg_setup_batched(int32_t nchains, const int64_t* chain_row_off,
 int bamg_solve_batched(bamg_handle h, double* x, double tol, int32_t max_cycles,
                        uint32_t flags, int32_t* chain_status,
                        double* chain_residual, bamg_solve_info* info);
+
+/* The multilevel eigensolver iteration used as a stand-alone solver (Section
+   4.1: the MLE steps of Algorithm 3 yield the state-vector approximation
+   V_0[:, 0]).  Runs further setup cycles on the handle's hierarchy (with
+   options.mu as set up), each fitting every P_l to U_l and the previous cycle's
+   eigenvector approximations V_l, until ||B x||_1 / ||x||_1 <= tol for x =
+   V_0[:, 0] / sum, or max_cycles cycles.  x: caller-owned device array of n
+   doubles, written with that x clamped to x >= 0 and scaled to sum 1.  info
+   (host, may be NULL): cycles = MLE cycles run, history = residual after each.
+   The handle keeps the last cycle's hierarchy (bamg_solve uses it).  Returns
+   BAMG_ENOCONV when the tolerance is not met, BAMG_EUNSUPPORTED for a handle
+   of several chains, BAMG_EINVAL for NULL pointers, tol <= 0 or max_cycles < 0. */
+int bamg_mle_iterate(bamg_handle h, double* x, double tol, int32_t max_cycles, bamg_solve_info* info);
 
 /* Release everything the handle owns.  NULL is allowed.  The handle's stream
    is drained first; its device buffers go back to the library's process-wide

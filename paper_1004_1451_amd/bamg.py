@@ -35,7 +35,7 @@ ERROR_NAMES = {EINVAL: "EINVAL", ENOTSTOCH: "ENOTSTOCH", EZERODIAG: "EZERODIAG",
 EXPORTS = ["bamg_options_default", "bamg_setup", "bamg_solve", "bamg_free", "bamg_last_error", "bamg_get_stats",
            "bamg_level_info_get", "bamg_export", "bamg_apply_vcycle", "bamg_relax", "bamg_setup_batched",
            "bamg_solve_batched", "bamg_trim", "bamg_mlp_init", "bamg_mlp_forward", "bamg_mlp_loss_grad",
-           "bamg_mlp_train"]
+           "bamg_mlp_train", "bamg_mle_iterate"]
 
 
 class BamgError(RuntimeError):
@@ -56,7 +56,7 @@ class Options(C.Structure):
                 ("mlp_weights", C.c_void_p), ("seed", C.c_uint64), ("mem_budget", C.c_size_t),
                 ("profile", C.c_int32), ("stop_after", C.c_int32), ("cycle_mode", C.c_int32),
                 ("setup_passes", C.c_int32), ("collect", C.c_int32), ("mlp_judge", C.c_float),
-                ("relax", C.c_int32), ("gs_omega", C.c_double)]
+                ("relax", C.c_int32), ("gs_omega", C.c_double), ("mu", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -111,6 +111,8 @@ def load():
     lib.bamg_setup.restype = C.c_int
     lib.bamg_solve.argtypes = [vp, vp, dbl, i32, C.c_uint32, C.POINTER(SolveInfo)]
     lib.bamg_solve.restype = C.c_int
+    lib.bamg_mle_iterate.argtypes = [vp, vp, dbl, i32, C.POINTER(SolveInfo)]
+    lib.bamg_mle_iterate.restype = C.c_int
     lib.bamg_free.argtypes = [vp]
     lib.bamg_free.restype = C.c_int
     lib.bamg_last_error.argtypes = []
@@ -196,6 +198,13 @@ class Hierarchy:
         info = SolveInfo()
         flags = (USE_GUESS if use_guess else 0) | (PARNOLDI if parnoldi else 0)
         rc = load().bamg_solve(self._h, C.c_void_p(x.data_ptr()), float(tol), int(max_cycles), flags, C.byref(info))
+        _check(rc, allow=(ENOCONV,))
+        return info
+
+    def mle_iterate(self, x, tol=1e-10, max_cycles=50):
+        """Stand-alone MLE iteration on this handle (bamg_mle_iterate)."""
+        info = SolveInfo()
+        rc = load().bamg_mle_iterate(self._h, C.c_void_p(x.data_ptr()), float(tol), int(max_cycles), C.byref(info))
         _check(rc, allow=(ENOCONV,))
         return info
 

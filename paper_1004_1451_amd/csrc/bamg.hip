@@ -292,6 +292,7 @@ struct bamg_ctx {
     virtual void level_info(int l, bamg_level_info* out) = 0;
     virtual void export_item(int l, int what, void* dst, size_t bytes) = 0;
     virtual void vcycle_apply(const double* f, double* e) = 0;
+    virtual int mle_iterate(double* x, double tol, int max_cycles, bamg_solve_info* info) = 0;
     hipStream_t s = nullptr;
     bamg_options o{};
     bamg_stats st{};
@@ -1021,11 +1022,14 @@ struct Engine : bamg_ctx {
         }
     }
 
-    void upleg() {
-        for (int l = (int)L.size() - 2; l >= 0; --l) {
+    // Up-leg step of level l (Algorithm 3): V_l = P_l V_{l+1} for the chains
+    // that continue below l, relaxed on (B_l - lam T_l) v = 0, then the
+    // eigenvalue approximations updated (Rayleigh quotients).
+    void upleg_level(int l) {
+        {
             auto& lv = L[l];
             auto& c = L[l + 1];
-            if (lv.ncont == 0) continue;
+            if (lv.ncont == 0) return;
             const int rows = lv.cont_rows;
             long long tot = (long long)rows * VS;
             FastDiv dR((uint32_t)VS);
@@ -1059,7 +1063,10 @@ struct Engine : bamg_ctx {
                 HIPCHK(hipGetLastError());
             }
         }
-        // x0 = V_0[:, 0] / sum per chain
+    }
+
+    // The setup's state-vector approximation x0 = V_0[:, 0] / sum per chain.
+    void state_from_v() {
         LAUNCH((k_get_col_t<T>), nblk(n), BAMG_BLK, s, (int)n, VS, 0, (const T*)L[0].V, x0);
         seg_reduce<RED_SUM>(x0, nullptr, sc);
         LAUNCH(k_seg_scale, nblk(n), BAMG_BLK, s, (int)n, (const ChainGeo*)L[0].dgeo, nch, (const int*)nullptr,
@@ -1099,6 +1106,77 @@ struct Engine : bamg_ctx {
         rp = nrp; ci = nci; val = nvv;
     }
 
+    // Algorithm 3 (bootamg_mle) from level l: relax U_l, then o.mu rounds of
+    // fit P_l (to U_l, joined by V_l from the second round on, or from the
+    // start when use_v), Q_l, B_{l+1}, T_{l+1} and U_{l+1} = R U_l, the
+    // recursion, and the up-leg step.  The bottom (l = depth - 1) forms every
+    // chain's coarsest inverse and eigenpairs (a chain whose coarsest level
+    // lies higher keeps its operator, so its repeats there change nothing).
+    // Returns false where options.stop_after ends the setup.
+    bool mle_level(int l, bool use_v, bool prof) {
+        if (l == (int)L.size() - 1) {
+            if (o.stop_after == 1) return false;
+            coarsest_inverse();
+            coarsest_eigs();
+            return o.stop_after != 2;
+        }
+        sweeps(l, L[l].U, r, o.nu_setup, prof && l == 0);
+        for (int m = 0; m < o.mu; ++m) {
+            build_level(l, (use_v || m > 0) ? 1 : 0, true, prof && l == 0);
+            if (!mle_level(l + 1, use_v, prof)) return false;
+            upleg_level(l);
+        }
+        return true;
+    }
+
+    // MLE iteration as a stand-alone solver (Section 4.1): cycles of
+    // Algorithm 3, each fitting P_l to U_l and the previous cycle's V_l, until
+    // the state-vector approximation meets the tolerance; x (caller-owned,
+    // length n) receives it clamped and scaled to sum one.  The handle keeps
+    // the last cycle's hierarchy.
+    int mle_iterate(double* x, double tol, int max_cycles, bamg_solve_info* info) override {
+        auto t0 = std::chrono::steady_clock::now();
+        if (nch != 1) fail(BAMG_EUNSUPPORTED, "the MLE iteration runs on single-chain handles");
+        bamg_solve_info inf{};
+        const int N = (int)n;
+        const ChainGeo* g0 = L[0].dgeo;
+        if (!rvec) rvec = A.alloc<double>(N);
+        auto residual = [&]() {
+            LAUNCH(k_spmv<double>, nblk(N), BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)x0, -1.0,
+                   rvec, RowMask{g0, nch, nullptr});
+            seg_reduce<RED_ABS>(rvec, nullptr, sc + 1);
+            seg_reduce<RED_ABS>(x0, nullptr, sc + 2);
+            std::vector<double> h = getn(sc, (size_t)SCS);
+            return h[1] / h[2];
+        };
+        double rel = residual();
+        while (!(rel <= tol) && inf.cycles < max_cycles) {
+            mle_level(0, true, false);
+            state_from_v();
+            ++inf.cycles;
+            rel = residual();
+            if (inf.history_len < 256) inf.history[inf.history_len++] = rel;
+            if (!(rel == rel)) fail(BAMG_EDEVICE, "MLE iteration: non-finite residual");
+        }
+        HIPCHK(hipMemcpyAsync(x, x0, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+        seg_reduce<RED_NEGSUM>(x, nullptr, sc + 5);
+        LAUNCH(k_clamp, nblk(N), BAMG_BLK, s, N, x);
+        seg_reduce<RED_SUM>(x, nullptr, sc);
+        LAUNCH(k_seg_scale, nblk(N), BAMG_BLK, s, N, g0, nch, (const int*)nullptr, (const double*)x,
+               (const double*)nullptr, (const double*)sc, SCS, 0, x);
+        LAUNCH(k_spmv<double>, nblk(N), BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)x, -1.0, rvec,
+               RowMask{g0, nch, nullptr});
+        seg_reduce<RED_ABS>(rvec, nullptr, sc + 1);
+        seg_reduce<RED_ABS>(x, nullptr, sc + 2);
+        std::vector<double> h = getn(sc, (size_t)SCS);
+        inf.residual_l1 = h[1] / h[2];
+        inf.clamped_mass = h[5];
+        inf.converged = inf.residual_l1 <= tol;
+        st.t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (info) *info = inf;
+        return inf.converged ? BAMG_OK : BAMG_ENOCONV;
+    }
+
     void setup(const int32_t* rp, const int32_t* ci, const double* val) override {
         auto t0 = std::chrono::steady_clock::now();
         A.s = s;
@@ -1121,16 +1199,9 @@ struct Engine : bamg_ctx {
                    L[0].nch, o.seed, L[0].U);
         }
         const int depth = (int)L.size();
-        // down-leg: relax, fit, Galerkin, inject
-        for (int l = 0; l + 1 < depth; ++l) {
-            sweeps(l, L[l].U, r, o.nu_setup, prof && l == 0);
-            build_level(l, 0, true, prof && l == 0);
-        }
-        if (o.stop_after == 1) { finish_setup(t0); return; }
-        coarsest_inverse();
-        coarsest_eigs();
-        if (o.stop_after == 2) { finish_setup(t0); return; }
-        upleg();
+        // one cycle of Algorithm 3 from the random test vectors
+        if (!mle_level(0, false, prof)) { finish_setup(t0); return; }
+        state_from_v();
         if (o.stop_after == 3 || o.setup_passes == 1) { finish_setup(t0); return; }
         // recompute every P, B, T from U u V
         for (int l = 0; l + 1 < depth; ++l) build_level(l, 1, false, prof && l == 0);
@@ -1740,6 +1811,7 @@ void check_options(const bamg_options& o) {
     if (o.precision != BAMG_FP64 && o.precision != BAMG_MIXED) fail(BAMG_EINVAL, "unknown precision %d", o.precision);
     if (o.relax != BAMG_RELAX_JACOBI && o.relax != BAMG_RELAX_MCGS) fail(BAMG_EINVAL, "unknown relaxation %d", o.relax);
     if (!(o.gs_omega > 0 && o.gs_omega < 2)) fail(BAMG_EINVAL, "gs_omega must lie in (0, 2)");
+    if (o.mu < 1 || o.mu > 2) fail(BAMG_EINVAL, "mu must be 1 (V-cycle) or 2 (W-cycle)");
 }
 
 bamg_ctx* make_ctx(const bamg_options& o) {
@@ -1818,6 +1890,7 @@ void bamg_options_default(bamg_options* opt) {
     opt->mlp_judge = 2.0f;
     opt->relax = BAMG_RELAX_JACOBI;
     opt->gs_omega = 1.0;
+    opt->mu = 1;
 }
 
 const char* bamg_last_error(void) { return g_last_error.c_str(); }
@@ -1863,6 +1936,18 @@ int bamg_solve_batched(bamg_handle h, double* x, double tol, int32_t max_cycles,
     });
     if (rc != BAMG_OK) return rc;
     if (code == BAMG_ENOCONV) g_last_error = "tolerance not reached within max_cycles for some chain";
+    return code;
+}
+
+int bamg_mle_iterate(bamg_handle h, double* x, double tol, int32_t max_cycles, bamg_solve_info* info) {
+    int code = BAMG_OK;
+    int rc = run_guarded([&] {
+        if (!h || !x) fail(BAMG_EINVAL, "NULL handle or x");
+        if (!(tol > 0) || max_cycles < 0) fail(BAMG_EINVAL, "invalid tol or max_cycles");
+        code = h->mle_iterate(x, tol, max_cycles, info);
+    });
+    if (rc != BAMG_OK) return rc;
+    if (code == BAMG_ENOCONV) g_last_error = "tolerance not reached within max_cycles MLE cycles";
     return code;
 }
 
