@@ -120,14 +120,10 @@ __global__ void k_cz_extract(const CoarseDesc* __restrict__ cd, const double* __
 // Inversion of one diagonal block: Gauss-Jordan elimination without
 // pivoting on the block padded to 64 x 64 with the identity.  Thread (w, c)
 // of CZ_GJ_THREADS keeps column c of rows CZ_GJ_ROWS w .. + CZ_GJ_ROWS - 1 in
-// registers.  Step st, for row r and column c (f = a_r,st, p = a_st,st):
-//   a_st,c <- a_st,c / p,  a_r,st <- -f / p,  a_st,st <- 1 / p,
-//   a_r,c <- a_r,c - f a_st,c / p  (all other entries).
-// Before the step's barrier the owner wave puts the pivot row and lane st of
-// every wave its part of the pivot column into LDS (two buffers, alternating),
-// so each thread then does one fused multiply-add per entry: the pivot column
-// takes a_r,st - f (1 + 1/p) = -f / p, and the owner rewrites the pivot row
-// afterwards.  1/p is v_rcp_f64 refined by two Newton steps.
+// registers.  Before each step's barrier the owner wave puts the pivot rows,
+// and the lanes of the pivot columns in every wave their parts of those
+// columns, into LDS (two buffers, alternating).  1/p is v_rcp_f64 refined by
+// two Newton steps.
 #define CZ_GJ_THREADS 256
 #define CZ_GJ_ROWS (GJ_NB * BAMG_WAVE / CZ_GJ_THREADS)
 __device__ __forceinline__ double cz_recip(double p) {
@@ -139,27 +135,48 @@ __device__ __forceinline__ double cz_recip(double p) {
 }
 
 // Gauss-Jordan on the 64 x 64 block held in S by the CZ_GJ_THREADS threads
-// (w = wave, c = lane); mp takes the smallest |pivot| / sc of the first nb.
+// (w = wave, c = lane), two pivots per step: with the pivot block
+// P = A[J, J], J = {s, s+1}, and its closed-form inverse Q,
+//   A[J, c] <- Q A[J, c],  A[r, J] <- -A[r, J] Q,  A[J, J] <- Q,
+//   A[r, c] <- A[r, c] - A[r, J] Q A[J, c]  (r, c outside J),
+// the same Schur complements as two scalar steps.  Each entry takes two
+// fused multiply-adds; the pivot columns use m = e_j + Q[:, j] so the same
+// update leaves -A[r, J] Q there.  mp takes the smallest |scalar pivot| / sc
+// of the first nb (a and det / a per block).
 __device__ __forceinline__ void cz_gj(double (&S)[CZ_GJ_ROWS], int w, int c, int nb, double sc, double& mp,
-                                      double (*prow)[GJ_NB], double (*pcol)[GJ_NB]) {
+                                      double (*prow)[2][GJ_NB], double (*pcol)[GJ_NB][2]) {
+    static_assert(CZ_GJ_ROWS % 2 == 0, "pivot pairs stay inside one wave");
     for (int blk = 0; blk < GJ_NB / CZ_GJ_ROWS; ++blk) {
 #pragma unroll
-        for (int ii = 0; ii < CZ_GJ_ROWS; ++ii) {
-            const int st = CZ_GJ_ROWS * blk + ii, buf = st & 1;
-            const bool ck = c == st;
-            if (w == blk) prow[buf][c] = S[ii];
-            if (ck)
+        for (int ss = 0; ss < CZ_GJ_ROWS / 2; ++ss) {
+            const int s0 = CZ_GJ_ROWS * blk + 2 * ss, buf = ss & 1;
+            const int j = c - s0;
+            const bool cj = j == 0 || j == 1;
+            if (w == blk) { prow[buf][0][c] = S[2 * ss]; prow[buf][1][c] = S[2 * ss + 1]; }
+            if (cj)
 #pragma unroll
-                for (int i = 0; i < CZ_GJ_ROWS; ++i) pcol[buf][CZ_GJ_ROWS * w + i] = S[i];
+                for (int i = 0; i < CZ_GJ_ROWS; ++i) pcol[buf][CZ_GJ_ROWS * w + i][j] = S[i];
             __syncthreads();
-            const double piv = prow[buf][st];
-            const double ip = cz_recip(piv);
-            const double pr = prow[buf][c] * ip;
-            const double pm = ck ? 1.0 + ip : pr;
-            if (threadIdx.x == 0 && st < nb) mp = fmin(mp, fabs(piv) / sc);
+            const double a = prow[buf][0][s0], b = prow[buf][0][s0 + 1];
+            const double cc = prow[buf][1][s0], d = prow[buf][1][s0 + 1];
+            const double det = fma(a, d, -b * cc);
+            const double id = cz_recip(det);
+            const double q00 = d * id, q01 = -b * id, q10 = -cc * id, q11 = a * id;
+            if (threadIdx.x == 0) {
+                if (s0 < nb) mp = fmin(mp, fabs(a) / sc);
+                if (s0 + 1 < nb) mp = fmin(mp, fabs(det / a) / sc);
+            }
+            const double r0 = prow[buf][0][c], r1 = prow[buf][1][c];
+            const double g0 = fma(q00, r0, q01 * r1), g1 = fma(q10, r0, q11 * r1);
+            const double p0 = j == 0 ? q00 : q01, p1 = j == 0 ? q10 : q11;     // column j of Q
+            const double m0 = cj ? (j == 0 ? 1.0 : 0.0) + p0 : g0;
+            const double m1 = cj ? (j == 1 ? 1.0 : 0.0) + p1 : g1;
 #pragma unroll
-            for (int i = 0; i < CZ_GJ_ROWS; ++i) S[i] = fma(-pcol[buf][CZ_GJ_ROWS * w + i], pm, S[i]);
-            if (w == blk) S[ii] = ck ? ip : pr;
+            for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+                const double2 f = *(const double2*)&pcol[buf][CZ_GJ_ROWS * w + i][0];
+                S[i] = fma(-f.x, m0, fma(-f.y, m1, S[i]));
+            }
+            if (w == blk) { S[2 * ss] = cj ? p0 : g0; S[2 * ss + 1] = cj ? p1 : g1; }
         }
     }
 }
@@ -279,8 +296,8 @@ k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, 
              double* __restrict__ minpiv) {
     static_assert(CZ_GJ_THREADS == BAMG_BLK, "one workgroup size for both parts");
     __shared__ double lds[2 * GJ_NB * (GJ_NB + 2)];
-    __shared__ double prow[2][GJ_NB];
-    __shared__ __align__(16) double pcol[2][GJ_NB];
+    __shared__ __align__(16) double prow[2][2][GJ_NB];
+    __shared__ __align__(16) double pcol[2][GJ_NB][2];
     const CoarseDesc d = cd[blockIdx.y];
     const int K = d.nx - 1, q = blockIdx.x;
     const int kk = k < 0 ? K : k;
