@@ -314,6 +314,21 @@ k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, 
     const int c = tid % BAMG_WAVE, w = tid / BAMG_WAVE;
     const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
     double* D = cz_blk(Fp, d, 0, kk);
+    // the diagonal block and the next multiplier block are read at once, so
+    // their latency hides behind the first product
+    const bool mult = !arrow && kk < K;
+    double* Lo1 = mult ? cz_blk(Fp, d, 2, kk + 1) : nullptr;
+    double Dv[CZ_GJ_ROWS], Lp[GJ_NB * GJ_NB / BAMG_BLK];
+#pragma unroll
+    for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+        const int r = CZ_GJ_ROWS * w + i;
+        Dv[i] = (r < b && c < b) ? D[r * b + c] : 0.0;
+    }
+#pragma unroll
+    for (int q4 = 0; q4 < GJ_NB * GJ_NB / BAMG_BLK; ++q4) {
+        const int e = tid + q4 * BAMG_BLK, r = e / GJ_NB, cc = e % GJ_NB;
+        Lp[q4] = (mult && r < b && cc < b) ? Lo1[r * b + cc] : 0.0;
+    }
     double S[CZ_GJ_ROWS];
     if (kk >= 1) {
         // Lo_k Up_{k-1} in 4 x 4 tiles, then through LDS into this
@@ -331,13 +346,13 @@ k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, 
 #pragma unroll
         for (int i = 0; i < CZ_GJ_ROWS; ++i) {
             const int r = CZ_GJ_ROWS * w + i;
-            S[i] = (r < b && c < b) ? D[r * b + c] - AsT[r][c] : (r == c ? 1.0 : 0.0);
+            S[i] = (r < b && c < b) ? Dv[i] - AsT[r][c] : (r == c ? 1.0 : 0.0);
         }
     } else {
 #pragma unroll
         for (int i = 0; i < CZ_GJ_ROWS; ++i) {
             const int r = CZ_GJ_ROWS * w + i;
-            S[i] = (r < b && c < b) ? D[r * b + c] : (r == c ? 1.0 : 0.0);
+            S[i] = (r < b && c < b) ? Dv[i] : (r == c ? 1.0 : 0.0);
         }
     }
     double mp = 1e300;
@@ -348,10 +363,13 @@ k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, 
         if (r < b && c < b) D[r * b + c] = S[i];
     }
     if (tid == 0) minpiv[blockIdx.y] = fmin(minpiv[blockIdx.y], mp);
-    if (!arrow && kk < K) {
-        double* Lo1 = cz_blk(Fp, d, 2, kk + 1);
+    if (mult) {
         __syncthreads();
-        cz_stage(b, Lo1, AsT, nullptr, Bs);
+#pragma unroll
+        for (int q4 = 0; q4 < GJ_NB * GJ_NB / BAMG_BLK; ++q4) {
+            const int e = tid + q4 * BAMG_BLK;
+            AsT[e % GJ_NB][e / GJ_NB] = Lp[q4];
+        }
 #pragma unroll
         for (int i = 0; i < CZ_GJ_ROWS; ++i) Bs[CZ_GJ_ROWS * w + i][c] = S[i];
         __syncthreads();
