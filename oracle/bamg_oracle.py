@@ -164,6 +164,143 @@ def is_c_point(g: Grid) -> np.ndarray:
     return ((s // g.ny) % 2 == 0) & ((s % g.ny) % 2 == 0)
 
 
+@dataclass
+class Coarsening:
+    """The C/F splitting of one level and the candidate sets N_i: ``isC`` per
+    point, ``cpts`` the fine index of every coarse point (ascending, so coarse
+    index = rank among the C points), ``slots`` (n, K) the coarse indices of
+    N_i, -1 where empty."""
+    isC: np.ndarray
+    cpts: np.ndarray
+    slots: np.ndarray
+    rounds: int = 0                              # CR relaxations performed
+    rho: list = field(default_factory=list)      # CR estimate of each
+
+    @property
+    def nc(self) -> int:
+        return len(self.cpts)
+
+
+def grid_coarsening(g: Grid) -> Coarsening:
+    """Full coarsening of a grid level (Section 5)."""
+    return Coarsening(is_c_point(g), c_points(g), neighbour_slots(g))
+
+
+# ---------------------------------------------------------------------------
+# Coarsening without a grid: compatible relaxation (Section 3.1, Algorithm 1,
+# eqs. frelax and meas1) from a standard independent set.
+# ---------------------------------------------------------------------------
+STREAM_CR = 16      # + level: the random start vectors of the CR relaxations
+
+
+def graph_of(B: sp.csr_matrix) -> sp.csr_matrix:
+    """G(B) without self-loops as a boolean CSR (edge i -> j for b_ij != 0).
+    The stored pattern counts, not the values.  The coarsening needs a
+    symmetric pattern (so that G(B) is an undirected graph); every coarse
+    operator Q B P then has one too."""
+    B = B.tocsr()
+    G = sp.csr_matrix((np.ones(B.nnz, dtype=bool), B.indices.copy(), B.indptr.copy()), shape=B.shape)
+    G.setdiag(False)
+    G.eliminate_zeros()
+    G.sort_indices()
+    if (G != G.T).nnz:
+        raise ValueError("coarsening without a grid needs a structurally symmetric matrix")
+    return G
+
+
+def independent_set(G: sp.csr_matrix, cand: np.ndarray) -> np.ndarray:
+    """Maximal independent set of the candidate points in graph G (the
+    standard independent set of Section 3.1): the candidates are visited in
+    increasing index and one joins when none of its neighbours has joined
+    (reading: index order, no weights)."""
+    taken = np.zeros(G.shape[0], dtype=bool)
+    ip, ix = G.indptr, G.indices
+    for i in np.nonzero(cand)[0]:
+        if not taken[ix[ip[i]:ip[i + 1]]].any():
+            taken[i] = True
+    return taken
+
+
+def f_relax(B: sp.csr_matrix, isC: np.ndarray, u: np.ndarray, omega: float, nu: int):
+    """nu sweeps of eq. frelax with omega-Jacobi, M = diag(B)/omega:
+    u_F <- u_F - omega D_FF^-1 B_FF u_F (the homogeneous F-relaxation; u stays
+    zero on C).  Returns (u^{nu-1}, u^nu)."""
+    F = ~isC
+    Bff = B[F][:, F]
+    s = omega / B.diagonal()[F]
+    uf = u[F].copy()
+    prev = uf
+    for _ in range(nu):
+        prev = uf
+        uf = uf - s * (Bff @ uf)
+    a = np.zeros_like(u); b = np.zeros_like(u)
+    a[F] = prev; b[F] = uf
+    return a, b
+
+
+def cr_coarsen(B: sp.csr_matrix, level: int, omega: float, theta: float, nu: int, seed: int,
+               max_rounds: int, C0: np.ndarray | None = None):
+    """Algorithm 1 (compatible_relaxation).  C starts from C0, by default the
+    independent set of all points in G(B).  Each round relaxes nu times from
+    u^0_i ~ U[1, 2] on F (zero on C; u^0 of round k at point i is
+    1 + u(seed, STREAM_CR + level, k n + i)) and estimates rho_f =
+    (||u^nu||_2 / ||u^0||_2)^(1/nu) (eq. meas1).  While rho_f > theta, the
+    F points with |u_i^nu| > theta |u_i^(nu-1)| (the ratio test written as a
+    product) form the candidate set N, and an independent set of N (in the
+    graph restricted to N) joins C.  Readings: the loop also ends when N is
+    empty and after max_rounds relaxations.  Returns (isC, rounds, rhos)."""
+    n = B.shape[0]
+    G = graph_of(B)
+    isC = independent_set(G, np.ones(n, dtype=bool)) if C0 is None else C0.astype(bool).copy()
+    rhos = []
+    for k in range(max_rounds):
+        F = ~isC
+        u0 = np.where(F, 1.0 + _splitmix_u01(seed, STREAM_CR + level, np.arange(n, dtype=np.uint64) + k * n), 0.0)
+        prev, last = f_relax(B, isC, u0, omega, nu)
+        n0 = np.sqrt(np.sum(u0 * u0))
+        rho = (np.sqrt(np.sum(last * last)) / n0) ** (1.0 / nu) if n0 > 0 else 0.0
+        rhos.append(rho)
+        if not rho > theta:
+            break
+        N = F & (np.abs(last) > theta * np.abs(prev))
+        if not N.any():
+            break
+        isC = isC | independent_set(G, N)
+    return isC, len(rhos), rhos
+
+
+def graph_slots(B: sp.csr_matrix, isC: np.ndarray, z: int) -> np.ndarray:
+    """N_i of eq. neighbor_def without a grid: the C points j != i reachable
+    from i by a path of length <= z in G(B), as coarse indices in ascending
+    order, padded with -1 to the largest |N_i|."""
+    G = graph_of(B).astype(np.int64)
+    reach = G.copy()
+    for _ in range(z - 1):
+        reach = ((reach + reach @ G) > 0).astype(np.int64)
+    reach = reach.tocsr()
+    reach.setdiag(0)
+    reach.eliminate_zeros()
+    reach.sort_indices()
+    cidx = np.cumsum(isC) - 1
+    lists = []
+    for i in range(B.shape[0]):
+        js = reach.indices[reach.indptr[i]:reach.indptr[i + 1]]
+        lists.append(cidx[js[isC[js]]])
+    K = max(1, max(len(x) for x in lists))
+    slots = np.full((B.shape[0], K), -1, dtype=np.int64)
+    for i, x in enumerate(lists):
+        slots[i, :len(x)] = x
+    return slots
+
+
+def cr_coarsening(B: sp.csr_matrix, level: int, opts) -> Coarsening:
+    """Coarsening of a level without a grid: compatible relaxation, then the
+    candidate sets N_i at graph distance <= opts.nbr_dist."""
+    isC, rounds, rhos = cr_coarsen(B, level, opts.omega, opts.cr_theta, opts.cr_nu, opts.seed, opts.cr_rounds)
+    slots = graph_slots(B, isC, opts.nbr_dist)
+    return Coarsening(isC, np.nonzero(isC)[0], slots, rounds, rhos)
+
+
 # ---------------------------------------------------------------------------
 # Relaxation: omega-Jacobi, M = diag(B)/omega (Section 3, eq. amg_relax).
 # ---------------------------------------------------------------------------
@@ -264,8 +401,9 @@ def _masked_solve(G: np.ndarray, rhs: np.ndarray, S: np.ndarray) -> np.ndarray:
     return np.linalg.solve(M, (rhs * S)[..., None])[..., 0]
 
 
-def ls_fit(X: np.ndarray, w: np.ndarray, g: Grid, caliber: int):
-    """Interpolation P (n_f x n_c) for full coarsening.
+def ls_fit(X: np.ndarray, w: np.ndarray, g, caliber: int, order: bool = False):
+    """Interpolation P (n_f x n_c) for a coarsening ``g``: a Grid (full
+    coarsening) or a Coarsening (isC, cpts, slots).
 
     C points get a unit row at their coarse index.  For every F point i with
     slots N_i: G_st = sum_k w_k x_s^k x_t^k, b_s = sum_k w_k x_s^k x_i^k,
@@ -276,27 +414,29 @@ def ls_fit(X: np.ndarray, w: np.ndarray, g: Grid, caliber: int):
     when its Schur-complement pivot G_gg - G_gJ G_JJ^-1 G_Jg exceeds
     1e-10 G_gg.  If no slot is admissible, the first slot gets weight 1.
     Weights p = G_JJ^-1 b_J.  Returns (P csr with ascending columns, J mask
-    (n, 4), slots (n, 4)).
+    (n, K), slots (n, K)), and with ``order`` also the (n, K) slot chosen at
+    each greedy step (-1 after the last).
     """
+    cs = grid_coarsening(g) if isinstance(g, Grid) else g
     n, R = X.shape
-    cg = g.coarse()
-    slots = neighbour_slots(g)
-    isC = is_c_point(g)
-    cpts = c_points(g)
+    slots, isC, cpts = cs.slots, cs.isC, cs.cpts
+    K = slots.shape[1]
+    nc = len(cpts)
     fine_of_coarse = cpts                       # coarse index -> fine index
     valid = slots >= 0
-    Xs = X[fine_of_coarse[np.where(valid, slots, 0)]]          # (n, 4, R)
+    Xs = X[fine_of_coarse[np.where(valid, slots, 0)]]          # (n, K, R)
     Xs = Xs * valid[:, :, None]
     G = np.einsum("pak,pbk,k->pab", Xs, Xs, w)
     b = np.einsum("pak,pk,k->pa", Xs, X, w)
     sigma = np.einsum("pk,pk,k->p", X, X, w)
 
-    J = np.zeros((n, 4), dtype=bool)
+    J = np.zeros((n, K), dtype=bool)
+    steps = np.full((n, K), -1, dtype=np.int64)
     done = isC.copy()
-    for _ in range(4):
+    for step in range(min(K, caliber)):
         best_L = np.full(n, np.inf)
         best_g = np.full(n, -1)
-        for s_ in range(4):
+        for s_ in range(K):
             cand = (~done) & valid[:, s_] & (~J[:, s_]) & (J.sum(1) < caliber)
             ix = np.nonzero(cand)[0]
             if len(ix) == 0:
@@ -316,28 +456,35 @@ def ls_fit(X: np.ndarray, w: np.ndarray, g: Grid, caliber: int):
             best_g[ix] = np.where(better, s_, best_g[ix])
         took = best_g >= 0
         J[np.nonzero(took)[0], best_g[took]] = True
+        steps[took, step] = best_g[took]
         done |= ~took
     fpts = np.nonzero((~isC) & (J.sum(1) > 0))[0]
-    p = np.zeros((n, 4))
+    p = np.zeros((n, K))
     p[fpts] = _masked_solve(G[fpts], b[fpts], J[fpts])
     empty = (~isC) & (J.sum(1) == 0)
+    if np.any(empty & ~valid[:, 0]):
+        raise ValueError("an F point has no coarse neighbour")
     J[empty, 0] = True
     p[empty, 0] = 1.0
 
     rows, cols, vals = [], [], []
     ci = np.nonzero(isC)[0]
-    rows.append(ci); cols.append((ci // g.ny // 2) * cg.ny + (ci % g.ny) // 2); vals.append(np.ones(len(ci)))
+    cidx = np.cumsum(isC) - 1
+    rows.append(ci); cols.append(cidx[ci]); vals.append(np.ones(len(ci)))
     fi = np.nonzero(~isC)[0]
-    for s_ in range(4):
+    for s_ in range(K):
         sel = fi[J[fi, s_]]
         rows.append(sel); cols.append(slots[sel, s_]); vals.append(p[sel, s_])
     rows = np.concatenate(rows); cols = np.concatenate(cols); vals = np.concatenate(vals)
-    P = sp.csr_matrix((vals, (rows, cols)), shape=(n, cg.n))
+    P = sp.csr_matrix((vals, (rows, cols)), shape=(n, nc))
     P.sort_indices()
     # structural pattern must hold even a weight that is exactly zero
-    pat = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(n, cg.n)).astype(bool)
+    pat = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(n, nc)).astype(bool)
     P = _with_pattern(P, pat)
     J[isC] = False
+    steps[isC] = -1
+    if order:
+        return P, J, slots, steps
     return P, J, slots
 
 
@@ -364,9 +511,10 @@ def galerkin(Q: sp.csr_matrix, M: sp.csr_matrix, P: sp.csr_matrix) -> sp.csr_mat
     return _with_pattern(Q @ (M @ P), pat)
 
 
-def inject(X: np.ndarray, g: Grid) -> np.ndarray:
-    """R x: the values at the coarse points (Section 1, step 4; injection)."""
-    return X[c_points(g)]
+def inject(X: np.ndarray, g) -> np.ndarray:
+    """R x: the values at the coarse points (Section 1, step 4; injection);
+    g is a Grid or a Coarsening."""
+    return X[c_points(g) if isinstance(g, Grid) else g.cpts]
 
 
 # ---------------------------------------------------------------------------
@@ -548,11 +696,16 @@ class Options:
     mu: int = 1                # cycle index of Algorithm 3: 1 = V, 2 = W
     relax: str = "jacobi"      # or "mcgs": multicolour Gauss-Seidel
     gs_omega: float = 1.0      # weight of the Gauss-Seidel update
+    # coarsening without a grid (Algorithm 1 and eq. neighbor_def)
+    cr_theta: float = 0.85     # CR tolerance theta
+    cr_nu: int = 8             # CR sweeps per estimate
+    cr_rounds: int = 64        # at most this many CR relaxations per level
+    nbr_dist: int = 1          # z: path length of the candidate sets N_i
 
 
 @dataclass
 class Level:
-    grid: Grid
+    grid: Grid | None          # None: no grid, coarsened by compatible relaxation
     B: sp.csr_matrix
     T: sp.csr_matrix
     P: sp.csr_matrix | None = None
@@ -560,6 +713,8 @@ class Level:
     J: np.ndarray | None = None
     U: np.ndarray | None = None       # relaxed random test vectors
     V: np.ndarray | None = None       # eigenvector approximations (real columns)
+    cs: Coarsening | None = None      # C/F splitting and N_i (None on the coarsest level)
+    decided: bool = False             # cs fixed (it is decided once, on the first pass)
 
 
 @dataclass
@@ -577,14 +732,37 @@ def build_level(lv: Level, X: np.ndarray, opts: Options):
     """One level of the hierarchy from test set X: weights, LS fit, Q,
     B_{l+1}, T_{l+1} (Algorithm 3)."""
     w = tv_weights(lv.B, X)
-    P, J, _ = ls_fit(X, w, lv.grid, opts.caliber)
+    P, J, _ = ls_fit(X, w, lv.cs, opts.caliber)
     Q = averaging_q(P)
     Bc = galerkin(Q, lv.B, P)
     Tc = galerkin(Q, lv.T, P)
     return P, Q, J, Bc, Tc
 
 
-def mle_cycle(levels: list, l: int, plan: list, opts: Options, use_v: bool):
+def _coarsening(levels: list, l: int, plan, opts: Options) -> Coarsening | None:
+    """The coarsening of level l, fixed the first time the level is reached;
+    None marks the coarsest level.  On a grid it follows the level plan;
+    without one (plan None) level l is coarsened by compatible relaxation
+    while l + 1 < opts.levels (or, with opts.levels = 0, while n_l >
+    opts.coarse_max)."""
+    lv = levels[l]
+    if lv.decided:
+        return lv.cs
+    if plan is not None:
+        cs = grid_coarsening(plan[l]) if l < len(plan) - 1 else None
+    else:
+        n = lv.B.shape[0]
+        more = (l + 1 < opts.levels) if opts.levels > 0 else (n > opts.coarse_max)
+        cs = cr_coarsening(lv.B, l, opts) if more else None
+        if cs is not None and not (1 <= cs.nc < n):
+            if opts.levels > 0:
+                raise ValueError("compatible relaxation cannot coarsen level %d to the requested depth" % l)
+            cs = None
+    lv.cs, lv.decided = cs, True
+    return cs
+
+
+def mle_cycle(levels: list, l: int, plan, opts: Options, use_v: bool):
     """Algorithm 3 (bootamg_mle) from level l.  levels[l] holds B_l, T_l and
     U_l (and V_l from an earlier cycle when use_v).  Relax U_l; then mu times:
     fit P_l to U_l (joined by V_l after the first round, or from the start
@@ -593,7 +771,7 @@ def mle_cycle(levels: list, l: int, plan: list, opts: Options, use_v: bool):
     relaxed on (B_l - lam T_l) v = 0 with lam updated.  The coarsest level
     solves its eigenproblem.  Returns the eigenvalue entries."""
     lv = levels[l]
-    if l == len(plan) - 1:
+    if _coarsening(levels, l, plan, opts) is None:
         _, entries, V = coarsest_eigs(lv.B.toarray(), lv.T.toarray(), opts.n_eig)
         lv.V = V
         return entries
@@ -606,10 +784,10 @@ def mle_cycle(levels: list, l: int, plan: list, opts: Options, use_v: bool):
         P, Q, J, Bc, Tc = build_level(lv, X, opts)
         lv.P, lv.Q, lv.J = P, Q, J
         if len(levels) == l + 1:
-            levels.append(Level(plan[l + 1], Bc, Tc))
+            levels.append(Level(plan[l + 1] if plan is not None else None, Bc, Tc))
         else:
             levels[l + 1].B, levels[l + 1].T = Bc, Tc
-        levels[l + 1].U = inject(lv.U, lv.grid)
+        levels[l + 1].U = inject(lv.U, lv.cs)
         entries = mle_cycle(levels, l + 1, plan, opts, use_v)
         gs = None
         if opts.relax == "mcgs":
@@ -620,10 +798,14 @@ def mle_cycle(levels: list, l: int, plan: list, opts: Options, use_v: bool):
     return entries
 
 
-def _first_level(A: sp.csr_matrix, grid: Grid, r: int, opts: Options):
-    plan = level_plan(grid, opts.levels, opts.coarse_max)
+def _first_level(A: sp.csr_matrix, grid: Grid | None, r: int, opts: Options):
+    """Level 0 with the random test vectors; grid None: no grid (compatible
+    relaxation coarsens every level)."""
+    if grid is None and opts.relax != "jacobi":
+        raise ValueError("multicolour Gauss-Seidel needs a grid")
+    plan = level_plan(grid, opts.levels, opts.coarse_max) if grid is not None else None
     n = A.shape[0]
-    lv = Level(plan[0], b_from_a(A.tocsr()), sp.identity(n, format="csr"))
+    lv = Level(grid, b_from_a(A.tocsr()), sp.identity(n, format="csr"))
     lv.U = initial_tvs(n, r, opts.seed)
     return plan, [lv]
 
@@ -636,7 +818,7 @@ def setup(A: sp.csr_matrix, grid: Grid, r: int, opts: Options) -> Hierarchy:
     first = [(lv.P, lv.B, lv.T) for lv in levels]
     x0 = levels[0].V[:, 0] / np.sum(levels[0].V[:, 0])
     # recompute every P, B, T from the enriched sets U u V
-    for l in range(len(plan) - 1):
+    for l in range(len(levels) - 1):
         lv = levels[l]
         X = np.concatenate([lv.U, lv.V], axis=1)
         P, Q, J, Bc, Tc = build_level(lv, X, opts)

@@ -7,6 +7,7 @@ none of the multilevel method's arithmetic, so both the GPU path and the CPU
 oracle may use it.
 
 State numbering is row-major on an ``nx x ny`` grid: state ``s = a*ny + b``.
+A chain without a grid (``nx = ny = 0``) is coarsened by compatible relaxation.
 
 Randomness is counter-based: ``uniform(seed, stream, idx)`` is the SplitMix64
 finaliser (Steele, Lea and Flood, OOPSLA 2014) applied to
@@ -31,6 +32,8 @@ STREAM_BATCH = 4
 STREAM_MLP_INIT = 5
 STREAM_MLP_SHUFFLE = 6
 STREAM_TRAIN_SIZES = 8   # (stream 7 is the coarsest Arnoldi start vector)
+STREAM_UPG = 9           # point coordinates of the unstructured planar graph
+# (streams 16 + l are the compatible-relaxation start vectors of level l)
 
 
 def splitmix64(key: np.ndarray) -> np.ndarray:
@@ -173,6 +176,30 @@ def weighted_lattice(m: int, seed: int = 0, periodic: bool = True, my: int | Non
     exact = deg / deg.sum()
     name = ("uniform" if uniform_weights else "lattice") + f"{m}" + ("p" if periodic else "")
     return Chain(n, row_ptr, col, val, m, my, periodic, name=name, exact=exact)
+
+
+def upg(N: int, seed: int = 0) -> Chain:
+    """Unstructured planar graph (Section 5, Table 4): the Delaunay
+    triangulation of ``N`` points in the unit square, point ``i`` at
+    ``(u(2i), u(2i+1))`` drawn from (seed, STREAM_UPG); from state ``j`` the walk
+    moves to each of its ``d_j`` triangulation neighbours with probability
+    ``1/d_j``.  It is reversible with stationary vector proportional to ``d``.
+    The points are numbered in the order drawn, so the numbering carries no
+    geometry; the chain has no grid (``nx = ny = 0``)."""
+    from scipy.spatial import Delaunay
+    xy = uniform(seed, STREAM_UPG, np.arange(2 * N)).reshape(N, 2)
+    tri = Delaunay(xy).simplices.astype(np.int64)
+    e = np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [0, 2]]])
+    e = np.sort(e, axis=1)
+    e = np.unique(e[:, 0] * N + e[:, 1])
+    ei, ej = e // N, e % N
+    deg = np.zeros(N)
+    np.add.at(deg, ei, 1.0)
+    np.add.at(deg, ej, 1.0)
+    dst = np.concatenate([ej, ei]); src = np.concatenate([ei, ej])
+    p = 1.0 / deg[src]
+    row_ptr, col, val = _csr_from_triplets(N, dst, src, p)
+    return Chain(N, row_ptr, col, val, 0, 0, False, name=f"upg{N}", exact=deg / deg.sum())
 
 
 def batch_mix(n_chains: int = 64, seed: int = 0):
