@@ -732,7 +732,7 @@ def build_level(lv: Level, X: np.ndarray, opts: Options):
     """One level of the hierarchy from test set X: weights, LS fit, Q,
     B_{l+1}, T_{l+1} (Algorithm 3)."""
     w = tv_weights(lv.B, X)
-    P, J, _ = ls_fit(X, w, lv.cs, opts.caliber)
+    P, J, _ = ls_fit(X, w, lv.cs if lv.cs is not None else lv.grid, opts.caliber)
     Q = averaging_q(P)
     Bc = galerkin(Q, lv.B, P)
     Tc = galerkin(Q, lv.T, P)
