@@ -24,6 +24,13 @@
  *     0 <= b < ny); coarsening keeps the points with a and b even.  Every
  *     nonzero of A must join states within Chebyshev distance 1 on that grid
  *     (with wrap-around when periodic).
+ *   - Or the chain has no grid (bamg_grid {0, 0, 0}; single-chain setup
+ *     only): compatible relaxation (Section 3.1, Algorithm 1) chooses the
+ *     coarse points of every level, starting from the standard independent
+ *     set of the matrix graph, and N_i holds the coarse points joined to i by
+ *     a stored entry (eq. neighbor_def with z = 1).  The pattern of A must be
+ *     symmetric (an undirected graph, like the unstructured planar graphs of
+ *     Section 5); omega-Jacobi relaxation and LS interpolation only.
  *   - "device" pointers are HIP device memory of the current device; "host"
  *     pointers are ordinary host memory.  The library never frees caller
  *     memory.  A handle owns everything it allocates and is bound to the
@@ -49,8 +56,11 @@ extern "C" {
 #define BAMG_EINVAL (-1)        /* bad argument, shape, pattern or grid      */
 #define BAMG_ENOTSTOCH (-2)     /* negative entry or |column sum - 1| > 1e-12 */
 #define BAMG_EZERODIAG (-3)     /* b_ii <= 0 (distributive relaxation is not built) */
-#define BAMG_EUNSUPPORTED (-4)  /* stencil wider than the 3x3 grid box, or a grid
-                                   that cannot be coarsened to the requested depth */
+#define BAMG_EUNSUPPORTED (-4)  /* stencil wider than the 3x3 grid box, a grid
+                                   that cannot be coarsened to the requested depth,
+                                   or (without a grid) an unsymmetric pattern, a
+                                   point with more than 16 coarse neighbours or a
+                                   coarse row needing more than 2048 products */
 #define BAMG_ENOMEM (-5)        /* device allocation failed or mem_budget exceeded */
 #define BAMG_EDEVICE (-6)       /* a HIP runtime error (message kept)         */
 #define BAMG_ENOCONV (-7)       /* tolerance not reached within max_cycles; x and
@@ -139,6 +149,13 @@ typedef struct {
                             V-cycle (default), 2 = W-cycle (every level fits,
                             recurses and brings the eigenvectors up twice, the
                             second time fitting to U and V)                   */
+    /* chains without a grid (bamg_grid {0, 0, 0}): compatible relaxation,
+       Section 3.1, Algorithm 1 */
+    double cr_theta;     /* CR tolerance theta (default 0.85)                  */
+    int32_t cr_nu;       /* F-relaxation sweeps per estimate (default 8)       */
+    int32_t cr_rounds;   /* at most this many CR relaxations per level (64)    */
+    int32_t nbr_dist;    /* z of eq. neighbor_def: path length of the candidate
+                            sets N_i (only 1 is built)                        */
 } bamg_options;
 
 typedef struct {
@@ -181,6 +198,8 @@ typedef struct {
     int64_t nnz_p;      /* entries of P_l (0 on the coarsest level)           */
     int32_t r;          /* columns of U_l                                     */
     int32_t n_v;        /* columns of V_l                                     */
+    int32_t cr_rounds;  /* CR relaxations that chose this level's C points
+                           (0 on grids and on the coarsest level)            */
 } bamg_level_info;
 
 /* Items of bamg_export (arrays of one level, copied to host memory). */
@@ -209,17 +228,26 @@ typedef struct {
                                order (lexicographic (da, db)); needs collect  */
 #define BAMG_X_SLOTW0 19    /* float[n*4] the first pass's fitted weights in slot
                                order (least-squares form); needs collect      */
+#define BAMG_X_CMAP 20      /* int32[n] (level without a grid, not the coarsest):
+                               coarse index of each C point (its rank among the
+                               C points), -1 for an F point                   */
+#define BAMG_X_CR_RHO 21    /* double[cr_rounds]: the estimate of eq. meas1 of
+                               every CR relaxation of the level               */
 
 /* Fill *opt with the defaults: levels 0, coarse_max 1024, nu_setup 4,
    V(2,2), omega 0.7, caliber 4, n_eig 6, arnoldi_m 40, gmres_m 50,
    FP64, LS interpolation, seed 0, no budget, no profiling, 2 setup passes,
-   mlp_judge 2, omega-Jacobi relaxation (gs_omega 1), mu 1. */
+   mlp_judge 2, omega-Jacobi relaxation (gs_omega 1), mu 1; without a grid
+   cr_theta 0.85, cr_nu 8, cr_rounds 64, nbr_dist 1 (Section 3.1). */
 void bamg_options_default(bamg_options* opt);
 
 /* Build the hierarchy for A (device CSR, see conventions) with r initial test
    vectors.  The caller's arrays are only read during the call and may be freed
    once it returns.  stream: a hipStream_t (NULL = default stream); every
    kernel of this handle runs on it.  On success *out owns the hierarchy.
+   grid {0, 0, 0}: no grid, coarsened by compatible relaxation (see the
+   conventions); levels then counts the levels to build (0: coarsen while
+   n_l > coarse_max) and EUNSUPPORTED reports a level CR cannot coarsen.
    Errors: EINVAL (null pointer, n < 1, r < 1, bad CSR, nx*ny != n),
    ENOTSTOCH, EZERODIAG, EUNSUPPORTED, ENOMEM, EDEVICE, ESINGULAR.
    Irreducibility is a precondition and is not checked. */

@@ -25,7 +25,7 @@ PARNOLDI = 2
 
 X_B_ROWPTR, X_B_COL, X_B_VAL, X_T_ROWPTR, X_T_COL, X_T_VAL = 1, 2, 3, 4, 5, 6
 X_P_COL, X_P_VAL, X_U, X_V, X_LAMBDA, X_VKIND, X_X0, X_W, X_Y, X_U0 = 7, 8, 9, 10, 11, 12, 13, 14, 15, 16
-X_FEATURES, X_SLOTW, X_SLOTW0 = 17, 18, 19
+X_FEATURES, X_SLOTW, X_SLOTW0, X_CMAP, X_CR_RHO = 17, 18, 19, 20, 21
 MLP_NPARAM = 6020
 
 ERROR_NAMES = {EINVAL: "EINVAL", ENOTSTOCH: "ENOTSTOCH", EZERODIAG: "EZERODIAG", EUNSUPPORTED: "EUNSUPPORTED",
@@ -56,7 +56,9 @@ class Options(C.Structure):
                 ("mlp_weights", C.c_void_p), ("seed", C.c_uint64), ("mem_budget", C.c_size_t),
                 ("profile", C.c_int32), ("stop_after", C.c_int32), ("cycle_mode", C.c_int32),
                 ("setup_passes", C.c_int32), ("collect", C.c_int32), ("mlp_judge", C.c_float),
-                ("relax", C.c_int32), ("gs_omega", C.c_double), ("mu", C.c_int32)]
+                ("relax", C.c_int32), ("gs_omega", C.c_double), ("mu", C.c_int32),
+                ("cr_theta", C.c_double), ("cr_nu", C.c_int32), ("cr_rounds", C.c_int32),
+                ("nbr_dist", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -90,7 +92,7 @@ class MlpTrainInfo(C.Structure):
 class LevelInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("nx", C.c_int32), ("ny", C.c_int32), ("periodic", C.c_int32),
                 ("nnz_b", C.c_int64), ("nnz_t", C.c_int64), ("nnz_p", C.c_int64), ("r", C.c_int32),
-                ("n_v", C.c_int32)]
+                ("n_v", C.c_int32), ("cr_rounds", C.c_int32)]
 
 
 _lib = None
@@ -227,7 +229,7 @@ class Hierarchy:
                  X_V: (n * li.n_v, np.float64), X_LAMBDA: (2 * li.n_v, np.float64), X_VKIND: (li.n_v, np.int32),
                  X_X0: (n, np.float64), X_W: (n * n, np.float64), X_Y: (n, np.float64),
                  X_U0: (n * li.r, np.float64), X_FEATURES: (n * 24, np.float32), X_SLOTW: (n * 4, np.float32),
-                 X_SLOTW0: (n * 4, np.float32)}
+                 X_SLOTW0: (n * 4, np.float32), X_CMAP: (n, np.int32), X_CR_RHO: (li.cr_rounds, np.float64)}
         cnt, dt = sizes[what]
         out = np.empty(int(cnt), dtype=dt)
         _check(load().bamg_export(self._h, int(l), int(what), out.ctypes.data_as(C.c_void_p), out.nbytes))

@@ -31,6 +31,7 @@
 #include "../../include/bamg.h"
 #include "common.h"
 #include "k_coarse.h"
+#include "k_cr.h"
 #include "k_dense.h"
 #include "k_learn.h"
 #include "k_mcgs.h"
@@ -272,6 +273,13 @@ struct Level {
     float* slotw0 = nullptr;         // collected first-pass slot weights (rows x 4)
     int* cnt = nullptr;
     bool zero_into_e2 = false;       // first smoothing sweep target (fixed buffers)
+    // levels without a grid (compatible relaxation)
+    bool decided = false;            // coarsening fixed (on the first pass)
+    int* cmap = nullptr;             // coarse index per row, -1 on F
+    int *qrp = nullptr, *qci = nullptr;   // Q: CSR over the next level's rows
+    T* qvv = nullptr;
+    int cr_rounds = 0;
+    std::vector<double> cr_rho;      // CR estimate of every relaxation round
 };
 
 struct ChainH {
@@ -312,6 +320,10 @@ struct Engine : bamg_ctx {
     int VS = 8;                      // row stride of the eigenvector blocks (a multiple of 4)
     int ncol = 4;                    // colours of the multicolour Gauss-Seidel sweeps
     bool mcgs = false;
+    bool unstructured = false;       // no grid: compatible relaxation coarsens every level
+    // compatible-relaxation work arrays (level-0 sized)
+    int *cr_st = nullptr, *cr_isc = nullptr, *cr_cand = nullptr, *cr_pos = nullptr, *cr_flag = nullptr;
+    double *cr_u0 = nullptr, *cr_ua = nullptr, *cr_ub = nullptr, *cr_part = nullptr, *cr_out = nullptr;
     // finest level in FP64 for the outer iteration
     int* b0rp = nullptr;
     int* b0ci = nullptr;
@@ -441,6 +453,7 @@ struct Engine : bamg_ctx {
                 const GridH& gh = ch.plan[l];
                 gg.off = off; gg.n = (int)gh.n();
                 gg.nx = gh.nx; gg.ny = gh.ny; gg.periodic = gh.periodic; gg.dy = FastDiv((uint32_t)gh.ny);
+                if (unstructured) { gg.nx = 0; gg.ny = 1; gg.dy = FastDiv(1u); }     // no grid
                 if ((int)ch.plan.size() > l + 1) {
                     const GridH& gc = ch.plan[l + 1];
                     gg.cn = (int)gc.n(); gg.ncx = gc.nx; gg.ncy = gc.ny; gg.dcy = FastDiv((uint32_t)gc.ny);
@@ -477,46 +490,73 @@ struct Engine : bamg_ctx {
         const int depth = (int)L.size();
         VS = (std::max(1, o.n_eig) + 1 + 3) / 4 * 4;     // padded for 16-byte row moves
         for (int l = 0; l < depth; ++l) {
-            auto& lv = L[l];
-            const int n_l = lv.rows;
-            lv.dgeo = A.upload(lv.geo);
-            if (l == 0) {
-                lv.B.cap = nnzA + n_l;
-            } else {
-                lv.B.cap = 9 * n_l;
-                lv.Tm.cap = 9 * n_l;
-                lv.Tm.rp = A.alloc<int>(n_l + 1);
+            alloc_level(l, nnzA);
+            if (L[l].ncont > 0) alloc_cont(l);
+        }
+        alloc_globals();
+        // without a grid the depth and the coarsest size are known only once
+        // compatible relaxation has coarsened every level
+        if (!unstructured) alloc_coarsest();
+    }
+
+    // Rows, operators (grid levels: 9 entries per row reserved; levels
+    // without a grid: allocated by their Galerkin product), vectors of level l.
+    void alloc_level(int l, int nnzA) {
+        auto& lv = L[l];
+        const int n_l = lv.rows;
+        lv.dgeo = A.upload(lv.geo);
+        if (l == 0) {
+            lv.B.cap = nnzA + n_l;
+        } else {
+            lv.B.cap = unstructured ? 0 : 9 * n_l;
+            lv.Tm.cap = unstructured ? 0 : 9 * n_l;
+            lv.Tm.rp = A.alloc<int>(n_l + 1);
+            if (lv.Tm.cap) {
                 lv.Tm.ci = A.alloc<int>(lv.Tm.cap);
                 lv.Tm.v = A.alloc<T>(lv.Tm.cap);
             }
-            lv.B.rp = A.alloc<int>(n_l + 1);
+        }
+        lv.B.rp = A.alloc<int>(n_l + 1);
+        if (lv.B.cap) {
             lv.B.ci = A.alloc<int>(lv.B.cap);
             lv.B.v = A.alloc<T>(lv.B.cap);
-            lv.dinv = A.alloc<T>(n_l);
-            lv.U = A.alloc<T>((size_t)n_l * r);
-            lv.V = A.alloc<T>((size_t)n_l * VS);
-            zero(lv.V, sizeof(T) * (size_t)n_l * VS);
-            lv.e = A.alloc<T>(n_l);
-            lv.e2 = A.alloc<T>(n_l);
-            lv.f = A.alloc<T>(n_l);
-            lv.r = A.alloc<T>(n_l);
-            if (lv.ncont > 0) {
-                const int nc = L[l + 1].rows;
-                lv.pc = A.alloc<int>((size_t)lv.cont_rows * 4);
-                lv.pv = A.alloc<T>((size_t)lv.cont_rows * 4);
-                lv.qc = A.alloc<int>((size_t)nc * 9);
-                lv.qv = A.alloc<T>((size_t)nc * 9);
-                lv.mask = A.alloc<unsigned short>(nc);
-                lv.qmask = A.alloc<unsigned short>(nc);
-                lv.jcnt = A.alloc<unsigned char>(lv.cont_rows);
-                if (o.collect) {
-                    lv.feat = A.alloc<float>((size_t)lv.cont_rows * 24);
-                    lv.slotw = A.alloc<float>((size_t)lv.cont_rows * 4);
-                    lv.slotw0 = A.alloc<float>((size_t)lv.cont_rows * 4);
-                }
-                lv.cnt = A.alloc<int>(nc);
-            }
         }
+        lv.dinv = A.alloc<T>(n_l);
+        lv.U = A.alloc<T>((size_t)n_l * r);
+        lv.V = A.alloc<T>((size_t)n_l * VS);
+        zero(lv.V, sizeof(T) * (size_t)n_l * VS);
+        lv.e = A.alloc<T>(n_l);
+        lv.e2 = A.alloc<T>(n_l);
+        lv.f = A.alloc<T>(n_l);
+        lv.r = A.alloc<T>(n_l);
+    }
+
+    // P, Q and the per-row work arrays of a level that has a next level.
+    void alloc_cont(int l) {
+        auto& lv = L[l];
+        const int nc = L[l + 1].rows;
+        lv.pc = A.alloc<int>((size_t)lv.cont_rows * 4);
+        lv.pv = A.alloc<T>((size_t)lv.cont_rows * 4);
+        lv.jcnt = A.alloc<unsigned char>(lv.cont_rows);
+        lv.cnt = A.alloc<int>(nc + 1);
+        if (unstructured) {
+            lv.qrp = A.alloc<int>(nc + 1);
+            lv.qci = A.alloc<int>((size_t)lv.cont_rows * 4);
+            lv.qvv = A.alloc<T>((size_t)lv.cont_rows * 4);
+            return;
+        }
+        lv.qc = A.alloc<int>((size_t)nc * 9);
+        lv.qv = A.alloc<T>((size_t)nc * 9);
+        lv.mask = A.alloc<unsigned short>(nc);
+        lv.qmask = A.alloc<unsigned short>(nc);
+        if (o.collect) {
+            lv.feat = A.alloc<float>((size_t)lv.cont_rows * 24);
+            lv.slotw = A.alloc<float>((size_t)lv.cont_rows * 4);
+            lv.slotw0 = A.alloc<float>((size_t)lv.cont_rows * 4);
+        }
+    }
+
+    void alloc_globals() {
         if (MIXED) {
             b0rp = A.alloc<int>(n + 1);
             b0ci = A.alloc<int>(L[0].B.cap);
@@ -534,17 +574,67 @@ struct Engine : bamg_ctx {
             learn_acc = A.alloc<double>(2);
             zero(learn_acc, 2 * sizeof(double));
         }
-        // coarsest descriptors: chain c's coarsest level is its last plan entry
+        lam = A.alloc<double>((size_t)nch * 2 * KV);
+        kind = A.alloc<int>((size_t)nch * KV);
+        ent_col = A.alloc<int>((size_t)nch * KV);
+        nvc = A.alloc<int>(nch);
+        nentc = A.alloc<int>(nch);
+        zero(nvc, sizeof(int) * nch);
+        zero(lam, sizeof(double) * nch * 2 * KV);
+        zero(kind, sizeof(int) * nch * KV);
+        zero(ent_col, sizeof(int) * nch * KV);
+        x0 = A.alloc<double>(n);
+        if (nch > 1) {
+            cmask = A.upload(std::vector<int>(nch, 1));
+        }
+        {
+            const size_t P = L[0].segp;
+            size_t need = 4096;
+            const size_t PC = L[0].cnp;
+            need = std::max(need, (size_t)nch * PC * 2 * WS);
+            need = std::max(need, (size_t)nch * PC * KV * 4);
+            need = std::max(need, (size_t)nch * P * (BAMG_BLK / BAMG_WAVE) * (o.gmres_m + 2));
+            need = std::max(need, (size_t)nch * 64);
+            part = A.alloc<double>(need);
+        }
+        sc = A.alloc<double>((size_t)nch * SCS);
+        wts = A.alloc<double>((size_t)nch * WS);
+        err = A.alloc<int>(4);
+        itmp = A.alloc<int>(n + 1);
+        bsum = A.alloc<int>(nblk(n) + 1);
+        total = A.alloc<int>(4);
+        sweep_tmp = A.alloc<T>((size_t)n * std::max(r, VS));
+        if (unstructured) {
+            for (int** p : {&cr_st, &cr_isc, &cr_cand}) *p = A.alloc<int>(n);
+            cr_pos = A.alloc<int>(n + 1);
+            cr_flag = A.alloc<int>(8);
+            for (double** p : {&cr_u0, &cr_ua, &cr_ub}) *p = A.alloc<double>(n);
+            cr_part = A.alloc<double>(2 * (size_t)CR_RED_BLOCKS);
+            cr_out = A.alloc<double>(2);
+        }
+    }
+
+    // Coarsest descriptors (chain c's coarsest level is its last plan entry)
+    // and the pools of the coarsest pseudo-inverse and eigensolve.
+    void alloc_coarsest() {
         long long woff = 0, boff = 0, aoff = 0;
         int voff = 0;
         AMmax = 0; maxnL = 0; nxmax = 0;
         dense_fallback = false;
+        cdh.clear();
         for (int c = 0; c < nch; ++c) {
             const auto& ch = chains[c];
             const int lc = (int)ch.plan.size() - 1;
             const GridH& gh = ch.plan[lc];
             CoarseDesc d{};
-            d.n = (int)gh.n(); d.nx = gh.nx; d.ny = gh.ny; d.periodic = gh.periodic; d.dy = FastDiv((uint32_t)gh.ny);
+            if (unstructured) {
+                // no grid: the dense inverse
+                d.n = L[lc].rows; d.nx = 0; d.ny = 0; d.periodic = 0; d.dy = FastDiv(1u);
+                dense_fallback = true;
+            } else {
+                d.n = (int)gh.n(); d.nx = gh.nx; d.ny = gh.ny; d.periodic = gh.periodic; d.dy = FastDiv((uint32_t)gh.ny);
+                if (gh.ny > GJ_NB || gh.nx > CZ_MAX_NX) dense_fallback = true;
+            }
             d.row0 = L[lc].geo[c].off;
             d.voff = voff;
             d.woff = woff;
@@ -553,7 +643,6 @@ struct Engine : bamg_ctx {
             d.am = (o.n_eig > 1) ? std::max(0, std::min({o.arnoldi_m, d.n - 1, HQR_MAXM})) : 0;
             d.brp = L[lc].B.rp; d.bci = L[lc].B.ci; d.bv = L[lc].B.v;
             d.trp = L[lc].Tm.rp; d.tci = L[lc].Tm.ci; d.tv = L[lc].Tm.v;
-            if (gh.ny > GJ_NB || gh.nx > CZ_MAX_NX) dense_fallback = true;
             voff += d.n;
             woff += (long long)d.n * d.n;
             boff += 5LL * d.nx * d.ny * d.ny;
@@ -588,36 +677,20 @@ struct Engine : bamg_ctx {
         sel_s = A.alloc<double>((size_t)nch * SS);
         nsel = A.alloc<int>((size_t)nch * NS);
         dots = A.alloc<double>((size_t)nch * DS);
-        lam = A.alloc<double>((size_t)nch * 2 * KV);
-        kind = A.alloc<int>((size_t)nch * KV);
-        ent_col = A.alloc<int>((size_t)nch * KV);
-        nvc = A.alloc<int>(nch);
-        nentc = A.alloc<int>(nch);
-        zero(nvc, sizeof(int) * nch);
-        zero(lam, sizeof(double) * nch * 2 * KV);
-        zero(kind, sizeof(int) * nch * KV);
-        zero(ent_col, sizeof(int) * nch * KV);
-        x0 = A.alloc<double>(n);
-        if (nch > 1) {
-            cmask = A.upload(std::vector<int>(nch, 1));
+    }
+
+    // The coarsest descriptors after the coarsest operators moved (a level
+    // without a grid reallocates a product that outgrew its arrays).
+    void refresh_coarse_desc() {
+        if (cdh.empty()) return;
+        for (int c = 0; c < nch; ++c) {
+            const int lc = (int)chains[c].plan.size() - 1;
+            auto& d = cdh[c];
+            d.brp = L[lc].B.rp; d.bci = L[lc].B.ci; d.bv = L[lc].B.v;
+            d.trp = L[lc].Tm.rp; d.tci = L[lc].Tm.ci; d.tv = L[lc].Tm.v;
         }
-        {
-            const size_t P = L[0].segp;
-            size_t need = 4096;
-            const size_t PC = L[0].cnp;
-            need = std::max(need, (size_t)nch * PC * 2 * WS);
-            need = std::max(need, (size_t)nch * PC * KV * 4);
-            need = std::max(need, (size_t)nch * P * (BAMG_BLK / BAMG_WAVE) * (o.gmres_m + 2));
-            need = std::max(need, (size_t)nch * 64);
-            part = A.alloc<double>(need);
-        }
-        sc = A.alloc<double>((size_t)nch * SCS);
-        wts = A.alloc<double>((size_t)nch * WS);
-        err = A.alloc<int>(4);
-        itmp = A.alloc<int>(n + 1);
-        bsum = A.alloc<int>(nblk(n) + 1);
-        total = A.alloc<int>(4);
-        sweep_tmp = A.alloc<T>((size_t)n * std::max(r, VS));
+        HIPCHK(hipMemcpyAsync(cd, cdh.data(), sizeof(CoarseDesc) * cdh.size(), hipMemcpyHostToDevice, s));
+        sync();
     }
 
     // Validate A and build B = I - A on the finest level.
@@ -833,6 +906,12 @@ struct Engine : bamg_ctx {
         tv_weights(l, use_v);
         std::pair<hipEvent_t, hipEvent_t> ev;
         if (profile) ev = ev_begin();
+        if (unstructured) {
+            fit_u(l, use_v, inject);
+            if (profile) ev_end(ev, ev_ls);
+            galerkin_u(l, profile);
+            return;
+        }
         if (!use_v && mlp_pk) {
             // learned form of the first pass: network proposal judged by the fit
             const int grid = std::min(learn_grid, nblk(lv.cont_rows));
@@ -1113,7 +1192,197 @@ struct Engine : bamg_ctx {
     // chain's coarsest inverse and eigenpairs (a chain whose coarsest level
     // lies higher keeps its operator, so its repeats there change nothing).
     // Returns false where options.stop_after ends the setup.
+    // ---- levels without a grid (Section 3.1) --------------------------------
+    // The coarsening needs an undirected graph: the pattern of B_0 must be
+    // symmetric (then every Q B P is symmetric too).
+    void check_symmetric() {
+        zero(err, sizeof(int) * 4);
+        LAUNCH(k_check_sym, nblk(n), BAMG_BLK, s, (int)n, (const int*)b0rp, (const int*)b0ci, err);
+        if (get1(err) & ERR_UNSYM)
+            fail(BAMG_EUNSUPPORTED, "coarsening without a grid needs a structurally symmetric A");
+    }
+
+    // Drop the captured cycle (its buffers moved); the next cycle recaptures.
+    void invalidate_graph() {
+        if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; }
+        if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
+    }
+
+    // Standard independent set of the candidates (cand == nullptr: every
+    // row) into cr_st, in rounds of the greedy order until none is open.
+    void independent_set(int nl, const int* rp, const int* ci, const int* cand) {
+        LAUNCH(k_mis_init, nblk(nl), BAMG_BLK, s, nl, cand, cr_st);
+        for (int rounds = 0;; rounds += 4) {
+            if (rounds > nl + 8) fail(BAMG_EDEVICE, "independent set did not finish in %d rounds", rounds);
+            zero(cr_flag + 1, 4 * sizeof(int));
+            for (int b = 0; b < 4; ++b)
+                LAUNCH(k_mis_round, nblk(nl), BAMG_BLK, s, nl, rp, ci, cr_st, cr_flag + 1 + b);
+            if (get1(cr_flag + 4) == 0) break;
+        }
+    }
+
+    // Algorithm 1 on level l: C from the independent set of all points, then
+    // rounds of nu F-relaxation sweeps from random u^0 (stream STREAM_CR + l,
+    // counter k n_l + i in round k); while the estimate of eq. meas1 exceeds
+    // theta, an independent set of the slow points joins C.  Leaves cmap on the
+    // level and returns the number of C points.
+    template <typename M>
+    int cr_coarsen_t(int l, const int* rp, const int* ci, const M* v) {
+        auto& lv = L[l];
+        const int nl = lv.rows;
+        const int nb = nblk(nl);
+        independent_set(nl, rp, ci, nullptr);
+        LAUNCH(k_mis_take, nb, BAMG_BLK, s, nl, (const int*)cr_st, 1, cr_isc);
+        lv.cr_rho.clear();
+        const int rb = std::min(CR_RED_BLOCKS, nb);
+        for (int k = 0; k < o.cr_rounds; ++k) {
+            LAUNCH(k_cr_start, nb, BAMG_BLK, s, nl, (const int*)cr_isc, (uint64_t)o.seed, STREAM_CR + (uint64_t)l,
+                   (uint64_t)k * (uint64_t)nl, cr_u0, cr_ua);
+            double* a = cr_ua;
+            double* b = cr_ub;
+            for (int it = 0; it < o.cr_nu; ++it) {
+                LAUNCH((k_cr_sweep<M>), nb, BAMG_BLK, s, nl, rp, ci, v, o.omega, (const int*)cr_isc, (const double*)a,
+                       b);
+                std::swap(a, b);
+            }
+            // a = u^nu, b = u^(nu-1)
+            LAUNCH(k_cr_ssq_partial, rb, BAMG_BLK, s, nl, (const double*)cr_u0, (const double*)a, cr_part);
+            LAUNCH(k_cr_ssq_final, 1, BAMG_WAVE, s, rb, (const double*)cr_part, cr_out);
+            std::vector<double> q = getn(cr_out, 2);
+            const double rho = q[0] > 0.0 ? std::pow(std::sqrt(q[1]) / std::sqrt(q[0]), 1.0 / o.cr_nu) : 0.0;
+            lv.cr_rho.push_back(rho);
+            if (!(rho > o.cr_theta)) break;
+            zero(cr_flag, sizeof(int));
+            LAUNCH(k_cr_cand, nb, BAMG_BLK, s, nl, (const int*)cr_isc, (const double*)b, (const double*)a,
+                   o.cr_theta, cr_cand, cr_flag);
+            if (get1(cr_flag) == 0) break;
+            independent_set(nl, rp, ci, cr_cand);
+            LAUNCH(k_mis_take, nb, BAMG_BLK, s, nl, (const int*)cr_st, 0, cr_isc);
+        }
+        lv.cr_rounds = (int)lv.cr_rho.size();
+        scan(nl, cr_isc, cr_pos);
+        const int nc = get1(cr_pos + nl);
+        if (!lv.cmap) lv.cmap = A.alloc<int>(nl);
+        LAUNCH(k_cr_cmap, nb, BAMG_BLK, s, nl, (const int*)cr_isc, (const int*)cr_pos, lv.cmap);
+        return nc;
+    }
+
+    int cr_coarsen(int l) {
+        if (l == 0) return cr_coarsen_t<double>(0, b0rp, b0ci, (const double*)b0v);
+        auto& lv = L[l];
+        return cr_coarsen_t<T>(l, lv.B.rp, lv.B.ci, (const T*)lv.B.v);
+    }
+
+    // Level l without a grid, reached for the first time: coarsen it while
+    // l + 1 < options.levels (levels = 0: while n_l > coarse_max), adding
+    // level l + 1; otherwise it is the coarsest level.
+    void decide_level(int l) {
+        auto& lv = L[l];
+        lv.decided = true;
+        const int nl = lv.rows;
+        bool more = o.levels > 0 ? (l + 1 < o.levels) : (nl > o.coarse_max);
+        if (more && (int)L.size() >= 63) fail(BAMG_EUNSUPPORTED, "more than 63 levels");
+        if (more) {
+            const int nc = cr_coarsen(l);
+            if (!(nc >= 1 && nc < nl)) {
+                if (o.levels > 0)
+                    fail(BAMG_EUNSUPPORTED, "compatible relaxation cannot coarsen level %d (%d of %d points coarse)", l,
+                         nc, nl);
+                more = false;
+            } else {
+                add_level(l, nc);
+            }
+        }
+        if (!more) alloc_coarsest();
+    }
+
+    void add_level(int l, int nc) {
+        L.emplace_back();
+        auto& lv = L[l];
+        auto& c = L[l + 1];
+        ChainGeo gg{};
+        gg.off = 0; gg.n = nc; gg.nx = 0; gg.ny = 1; gg.periodic = 0; gg.dy = FastDiv(1u);
+        gg.coff = 0; gg.cn = 0; gg.ncx = 1; gg.ncy = 1; gg.dcy = FastDiv(1u);
+        c.geo = {gg};
+        c.nch = 1; c.ncont = 0;
+        c.rows = nc; c.cont_rows = 0;
+        c.segp = ceil_div(nc, SEG_ROWS);
+        c.cnp = ceil_div(nc, CN_ROWS);
+        c.zero_into_e2 = ((std::max(0, o.nu_pre - 1) + o.nu_post) % 2) == 1;
+        lv.ncont = 1;
+        lv.cont_rows = lv.rows;
+        lv.geo[0].cn = nc; lv.geo[0].coff = 0; lv.geo[0].ncx = 1; lv.geo[0].ncy = 1; lv.geo[0].dcy = FastDiv(1u);
+        HIPCHK(hipMemcpyAsync(lv.dgeo, lv.geo.data(), sizeof(ChainGeo), hipMemcpyHostToDevice, s));
+        chains[0].plan.push_back(GridH{nc, 1, 0});
+        alloc_level(l + 1, 0);
+        alloc_cont(l);
+        sync();
+    }
+
+    // Interpolation and averaging restriction of a level without a grid.
+    void fit_u(int l, int use_v, bool inject) {
+        auto& lv = L[l];
+        auto& c = L[l + 1];
+        const int nl = lv.cont_rows;
+        zero(err, sizeof(int) * 4);
+        LAUNCH((k_ls_fit_u<T, T>), ceil_div(nl, LSU_BLK), LSU_BLK, s, nl, r, use_v ? nvc_h[0] : 0, VS,
+               (const T*)lv.U, (const T*)lv.V, (const double*)wts, o.caliber, (const int*)lv.cmap,
+               (const int*)lv.B.rp, (const int*)lv.B.ci, lv.pc, lv.pv, inject ? c.U : (T*)nullptr, lv.jcnt, err);
+        const int e = get1(err);
+        if (e & ERR_NOCOARSE) fail(BAMG_EDEVICE, "an F point of level %d has no coarse neighbour", l);
+        if (e & ERR_WIDEN) fail(BAMG_EUNSUPPORTED, "a point of level %d has more than %d coarse neighbours", l, LSU_K);
+        const int nc = c.rows;
+        zero(lv.cnt, sizeof(int) * nc);
+        LAUNCH(k_qu_count, nblk(nl), BAMG_BLK, s, nl, (const int*)lv.pc, lv.cnt);
+        scan(nc, lv.cnt, lv.qrp);
+        zero(lv.cnt, sizeof(int) * nc);
+        LAUNCH(k_qu_fill, nblk(nl), BAMG_BLK, s, nl, (const int*)lv.pc, (const int*)lv.qrp, lv.cnt, lv.qci);
+        LAUNCH((k_qu_finish<T>), nblk(nc), BAMG_BLK, s, nc, (const int*)lv.qrp, lv.qci, (const unsigned char*)lv.jcnt,
+               lv.qvv);
+    }
+
+    // B_{l+1} = Q (B P), T_{l+1} = Q (T P) for a level without a grid: count,
+    // scan, (re)allocate when the product outgrew its arrays, fill.
+    void galerkin_u(int l, bool profile) {
+        auto& f = L[l];
+        auto& c = L[l + 1];
+        const int nc = c.rows;
+        bool moved = false;
+        for (int which = 0; which < 2; ++which) {
+            Csr<T>& M = which == 0 ? f.B : f.Tm;
+            Csr<T>& Cm = which == 0 ? c.B : c.Tm;
+            zero(err, sizeof(int) * 4);
+            LAUNCH((k_ugal<T>), nc, BAMG_WAVE, s, nc, 0, (const int*)f.qrp, (const int*)f.qci, (const T*)f.qvv,
+                   (const int*)M.rp, (const int*)M.ci, (const T*)M.v, (const int*)f.pc, (const T*)f.pv, f.cnt,
+                   (const int*)nullptr, (int*)nullptr, (T*)nullptr, err);
+            scan(nc, f.cnt, Cm.rp);
+            const int tot = get1(Cm.rp + nc);
+            if (get1(err) & ERR_GALCAP)
+                fail(BAMG_EUNSUPPORTED, "a row of the level-%d Galerkin product needs more than %d products", l + 1,
+                     UG_CAP);
+            if (tot > Cm.cap) {
+                Cm.cap = tot + tot / 4;
+                Cm.ci = A.alloc<int>(Cm.cap);
+                Cm.v = A.alloc<T>(Cm.cap);
+                moved = true;
+            }
+            std::pair<hipEvent_t, hipEvent_t> ev;
+            if (profile) ev = ev_begin();
+            LAUNCH((k_ugal<T>), nc, BAMG_WAVE, s, nc, 1, (const int*)f.qrp, (const int*)f.qci, (const T*)f.qvv,
+                   (const int*)M.rp, (const int*)M.ci, (const T*)M.v, (const int*)f.pc, (const T*)f.pv, f.cnt,
+                   (const int*)Cm.rp, Cm.ci, Cm.v, err);
+            if (profile) ev_end(ev, ev_gal);
+        }
+        zero(err, sizeof(int) * 4);
+        LAUNCH(k_dinv<T>, nblk(nc), BAMG_BLK, s, nc, c.B.rp, c.B.ci, c.B.v, o.omega, c.dinv, err);
+        if (moved) {
+            invalidate_graph();
+            if (l + 2 == (int)L.size()) refresh_coarse_desc();
+        }
+    }
+
     bool mle_level(int l, bool use_v, bool prof) {
+        if (unstructured && !L[l].decided) decide_level(l);
         if (l == (int)L.size() - 1) {
             if (o.stop_after == 1) return false;
             coarsest_inverse();
@@ -1187,10 +1456,13 @@ struct Engine : bamg_ctx {
         sync();
         if (hr[0] != 0 || hr[1] < 0) fail(BAMG_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] >= 0");
         const int nnzA = hr[1];
+        unstructured = nch == 1 && chains[0].grid.nx == 0;
+        L.reserve(64);                   // levels are added in place while coarsening
         plan_levels();
         allocate(nnzA);
         if (nch > 1) reorder_input(rp, ci, val, nnzA);
         build_b0(rp, ci, val, nnzA);
+        if (unstructured) check_symmetric();
         check_colours(0);
         const bool prof = o.profile != 0;
         {
@@ -1198,12 +1470,12 @@ struct Engine : bamg_ctx {
             LAUNCH(k_tv_init<T>, nblk(tot), BAMG_BLK, s, tot, r, FastDiv((uint32_t)r), (const ChainGeo*)L[0].dgeo,
                    L[0].nch, o.seed, L[0].U);
         }
-        const int depth = (int)L.size();
         // one cycle of Algorithm 3 from the random test vectors
         if (!mle_level(0, false, prof)) { finish_setup(t0); return; }
         state_from_v();
         if (o.stop_after == 3 || o.setup_passes == 1) { finish_setup(t0); return; }
         // recompute every P, B, T from U u V
+        const int depth = (int)L.size();
         for (int l = 0; l + 1 < depth; ++l) build_level(l, 1, false, prof && l == 0);
         coarsest_inverse();
         finish_setup(t0);
@@ -1302,9 +1574,13 @@ struct Engine : bamg_ctx {
         }
         LAUNCH((k_residual<T, T>), nb, BAMG_BLK, s, rows, lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const T*)cur,
                (const T*)lv.f, lv.r, mk);
-        LAUNCH(k_restrict_box<T>, nblk(c.rows), BAMG_BLK, s, c.rows, (const ChainGeo*)c.dgeo,
-               (const ChainGeo*)lv.dgeo, c.nch, (const unsigned short*)lv.qmask, (const unsigned char*)lv.jcnt,
-               (const T*)lv.r, c.f, (const int*)cmask);
+        if (unstructured)
+            LAUNCH(k_restrict_csr<T>, nblk(c.rows), BAMG_BLK, s, c.rows, (const int*)lv.qrp, (const int*)lv.qci,
+                   (const T*)lv.qvv, (const T*)lv.r, c.f);
+        else
+            LAUNCH(k_restrict_box<T>, nblk(c.rows), BAMG_BLK, s, c.rows, (const ChainGeo*)c.dgeo,
+                   (const ChainGeo*)lv.dgeo, c.nch, (const unsigned short*)lv.qmask, (const unsigned char*)lv.jcnt,
+                   (const T*)lv.r, c.f, (const int*)cmask);
         vcycle(l + 1);
         LAUNCH((k_prolong_add<T, T>), nb, BAMG_BLK, s, rows, lv.pc, (const T*)lv.pv, (const T*)c.e, cur, mk);
         if (mcgs) {
@@ -1703,7 +1979,8 @@ struct Engine : bamg_ctx {
         auto& lv = L[l];
         memset(out, 0, sizeof *out);
         out->n = lv.rows;
-        out->nx = lv.geo[0].nx; out->ny = lv.geo[0].ny; out->periodic = lv.geo[0].periodic;
+        out->nx = lv.geo[0].nx; out->ny = unstructured ? 0 : lv.geo[0].ny; out->periodic = lv.geo[0].periodic;
+        out->cr_rounds = lv.cr_rounds;
         out->nnz_b = get1(lv.B.rp + lv.rows);
         if (lv.Tm.rp) out->nnz_t = get1(lv.Tm.rp + lv.rows);
         if (lv.pc) out->nnz_p = 4LL * lv.cont_rows;
@@ -1776,6 +2053,14 @@ struct Engine : bamg_ctx {
                 copy_out(what == BAMG_X_SLOTW0 || o.setup_passes == 1 ? lv.slotw0 : lv.slotw, (size_t)rows * 4, dst,
                          bytes);
                 break;
+            case BAMG_X_CMAP:
+                if (!lv.cmap) fail(BAMG_EINVAL, "level %d was not coarsened by compatible relaxation", l);
+                copy_out(lv.cmap, rows, dst, bytes);
+                break;
+            case BAMG_X_CR_RHO:
+                if (bytes < lv.cr_rho.size() * sizeof(double)) fail(BAMG_EINVAL, "export buffer too small");
+                if (!lv.cr_rho.empty()) memcpy(dst, lv.cr_rho.data(), lv.cr_rho.size() * sizeof(double));
+                break;
             default: fail(BAMG_EINVAL, "unknown export item %d", what);
         }
     }
@@ -1814,6 +2099,17 @@ void check_options(const bamg_options& o) {
     if (o.mu < 1 || o.mu > 2) fail(BAMG_EINVAL, "mu must be 1 (V-cycle) or 2 (W-cycle)");
 }
 
+// The options a chain without a grid needs (compatible relaxation).
+void check_options_cr(const bamg_options& o) {
+    if (!(o.cr_theta > 0 && o.cr_theta < 1)) fail(BAMG_EINVAL, "cr_theta must lie in (0, 1)");
+    if (o.cr_nu < 1 || o.cr_nu > 1000 || o.cr_rounds < 1 || o.cr_rounds > 100000)
+        fail(BAMG_EINVAL, "cr_nu and cr_rounds must be positive");
+    if (o.nbr_dist != 1) fail(BAMG_EUNSUPPORTED, "candidate sets at graph distance %d are not built (only 1)", o.nbr_dist);
+    if (o.caliber > 4) fail(BAMG_EUNSUPPORTED, "caliber above 4 without a grid");
+    if (o.relax != BAMG_RELAX_JACOBI) fail(BAMG_EUNSUPPORTED, "multicolour Gauss-Seidel needs a grid");
+    if (o.interp != BAMG_INTERP_LS) fail(BAMG_EUNSUPPORTED, "the learned interpolation needs a grid");
+}
+
 bamg_ctx* make_ctx(const bamg_options& o) {
     if (o.precision == BAMG_MIXED) return new Engine<float>();
     return new Engine<double>();
@@ -1840,6 +2136,17 @@ int setup_common(int32_t nchains, const int64_t* off, const int32_t* row_ptr, co
             const bamg_grid& gr = grids[c];
             const long long nc = off[c + 1] - off[c];
             if (nc < 1) fail(BAMG_EINVAL, "chain %d is empty", c);
+            if (gr.nx == 0 && gr.ny == 0) {
+                // no grid: compatible relaxation decides every level
+                if (nchains != 1) fail(BAMG_EUNSUPPORTED, "chains without a grid are set up one at a time");
+                check_options_cr(o);
+                ch[c].uidx = c;
+                ch[c].uoff = off[c];
+                ch[c].n = nc;
+                ch[c].grid = GridH{0, 0, 0};
+                ch[c].plan = {GridH{(int)nc, 1, 0}};
+                continue;
+            }
             if (gr.nx < 1 || gr.ny < 1 || (long long)gr.nx * gr.ny != nc)
                 fail(BAMG_EINVAL, "grid %dx%d of chain %d does not match its %lld states", gr.nx, gr.ny, c, nc);
             if (gr.periodic && (gr.nx < 3 || gr.ny < 3)) fail(BAMG_EUNSUPPORTED, "periodic sides must be >= 3");
@@ -1891,6 +2198,10 @@ void bamg_options_default(bamg_options* opt) {
     opt->relax = BAMG_RELAX_JACOBI;
     opt->gs_omega = 1.0;
     opt->mu = 1;
+    opt->cr_theta = 0.85;
+    opt->cr_nu = 8;
+    opt->cr_rounds = 64;
+    opt->nbr_dist = 1;
 }
 
 const char* bamg_last_error(void) { return g_last_error.c_str(); }

@@ -107,7 +107,8 @@ __host__ __device__ __forceinline__ int ceil_div(long long a, long long b) { ret
 // a prefix of the rows.  One record per chain and level:
 struct ChainGeo {
     int off, n;             // rows of this chain on this level
-    int nx, ny, periodic;   // its grid (state s = a*ny + b, local numbering)
+    int nx, ny, periodic;   // its grid (state s = a*ny + b, local numbering);
+                            // nx = 0 (ny = 1): no grid
     FastDiv dy;             // division by ny
     int coff, cn;           // its rows on the next level (cn = 0: coarsest here)
     int ncx, ncy;           // next-level grid

@@ -691,13 +691,25 @@ __global__ void k_cz_project(const CoarseDesc* __restrict__ cd, double* __restri
 }
 
 // c_j = sum_i T_L[i, j] (T = I: c = 1), gathered from the 3x3 box rows in
-// ascending row order.
+// ascending row order.  Without a grid (nx = 0) the pattern of T_L is
+// symmetric, so the rows holding column j are the columns of row j.
 template <typename M>
 __global__ void k_cz_colsum(const CoarseDesc* __restrict__ cd, double* __restrict__ c) {
     const CoarseDesc d = cd[blockIdx.y];
     for (int j = blockIdx.x * BAMG_BLK + threadIdx.x; j < d.n; j += gridDim.x * BAMG_BLK) {
         if (!d.trp) { c[d.voff + j] = 1.0; continue; }
         const M* tv = (const M*)d.tv;
+        if (d.nx == 0) {
+            double sum = 0;
+            const int gj = d.row0 + j;
+            for (int q = d.trp[gj]; q < d.trp[gj + 1]; ++q) {
+                const int gi = d.tci[q];
+                for (int p = d.trp[gi]; p < d.trp[gi + 1]; ++p)
+                    if (d.tci[p] == gj) sum += (double)tv[p];
+            }
+            c[d.voff + j] = sum;
+            continue;
+        }
         int ja = (int)d.dy.div((uint32_t)j), jb = j - ja * d.ny;
         int rows[9];
 #pragma unroll

@@ -59,10 +59,12 @@ __global__ void k_check_a(int n, const int* __restrict__ rp, const int* __restri
         if (j < g.off || j >= g.off + g.n || j <= prev) { e |= ERR_RANGE; break; }
         prev = j;
         if (!(a >= 0.0) || !(a <= 1.0 + 1e-12)) e |= ERR_NEG;
-        int lj = j - g.off;
-        int ja = (int)g.dy.div((uint32_t)lj), jb = lj - ja * g.ny;
-        int da = grid_delta(ia, ja, g.nx, g.periodic), db = grid_delta(ib, jb, g.ny, g.periodic);
-        if (da < -1 || da > 1 || db < -1 || db > 1) e |= ERR_WIDE;
+        if (g.nx > 0) {          // nx = 0: a chain without a grid
+            int lj = j - g.off;
+            int ja = (int)g.dy.div((uint32_t)lj), jb = lj - ja * g.ny;
+            int da = grid_delta(ia, ja, g.nx, g.periodic), db = grid_delta(ib, jb, g.ny, g.periodic);
+            if (da < -1 || da > 1 || db < -1 || db > 1) e |= ERR_WIDE;
+        }
         if (j == i) has_diag = true;
         atomicAdd(&colsum[j], a);
     }
