@@ -97,6 +97,49 @@ def cpu_baseline_batch(chains, args, budget_s=15.0):
             "converged": conv}
 
 
+def cpu_baseline_upg(ch, args, budget_s=20.0):
+    """The oracle, untuned, on the same unstructured planar graph (whole
+    method, one thread), repeated while under budget_s; graphs above 16384
+    points are sampled by the graph of 16384 points scaled by the ratio of
+    point counts."""
+    from threadpoolctl import threadpool_limits
+    from oracle import bamg_oracle as O
+    from paper_1004_1451_amd import chains as C
+    sample = ch if ch.n <= 16384 else C.upg(16384, seed=0)
+    reps, dt = 0, 0.0
+    with threadpool_limits(limits=1):
+        while reps == 0 or (dt < budget_s / 4 and reps < 5):
+            t0 = time.perf_counter()
+            _, info, _ = O.stationary(sample.to_scipy(), None, args.r, O.Options(levels=args.levels), tol=args.tol,
+                                      max_cycles=200)
+            dt += time.perf_counter() - t0
+            reps += 1
+    per = dt / reps
+    scale = ch.n / sample.n
+    return {"value": per * scale, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle setup+solve on the Delaunay graph of {sample.n} points ({args.levels} levels, r={args.r}, "
+                      f"tol={args.tol:g}, {info.cycles} cycles), mean of {reps} run(s) on 1 thread: {per:.3f} s"
+                      + (f"; scaled by point ratio {scale:.1f} (linear: the oracle's dense coarsest SVD grows "
+                         f"faster, so this understates the oracle)" if scale != 1 else ""),
+            "converged": bool(info.converged)}
+
+
+PEAK_FP64_TFLOPS = 78.6
+
+
+def _roofline_dense(stats):
+    """Rank-64 updates of the dense coarsest Gauss-Jordan inverse: flops / HIP
+    event time of those launches (FP64 vector FMAs) against the FP64 peak."""
+    ms = sum(s.dense_update_ms for s in stats)
+    n = sum(s.dense_update_launches for s in stats)
+    flops = sum(s.dense_update_flops for s in stats)
+    achieved = flops / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+            "kernel": "k_gj_update (rank-64 update of the dense coarsest inverse, FP64)",
+            "flops_per_launch": round(flops / max(1, n)), "mean_launch_us": round(ms * 1e3 / max(1, n), 2)}
+
+
 def _roofline(stats, traffic):
     sweep_ms = sum(s.sweep_ms for s in stats) / max(1, sum(s.sweep_launches for s in stats))
     sweep_bytes = stats[-1].sweep_bytes
@@ -143,16 +186,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["tandem", "batch64", "learned"], default="tandem",
+    ap.add_argument("--workload", choices=["tandem", "batch64", "learned", "upg"], default="tandem",
                     help="tandem: one tandem queue (default N=2047, n=4.2M); batch64: 64 mixed chains in one handle; "
                          "learned: train the interpolation network on 32 jittered tandems (untimed), then time the "
                          "learned form on the tandem queue against the plain forms")
     ap.add_argument("--train-chains", type=int, default=32)
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--N", type=int, default=2047, help="tandem queue capacity (side N+1)")
-    ap.add_argument("--levels", type=int, default=6)
-    ap.add_argument("--r", type=int, default=12)
-    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--levels", type=int, default=None, help="6 (tandem, learned), 3 (upg)")
+    ap.add_argument("--r", type=int, default=None, help="test vectors: 12, or 6 for upg (Table 4)")
+    ap.add_argument("--tol", type=float, default=None, help="1e-10, or 1e-8 for upg (Table 4)")
+    ap.add_argument("--upg-n", type=int, default=65536,
+                    help="upg workload: points of the Delaunay triangulation (Table 4 goes to 2048; 65536 fills "
+                         "the GPU better)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed",
                     help="mixed (default): FP32 relaxation, Galerkin products and cycle, FP64 coarsest level, norms "
                          "and outer iteration; fp64: every step in FP64")
@@ -169,6 +215,13 @@ def main():
                     help="only run three plain device copies of MIB MiB (the reference kernel whose FETCH_SIZE / "
                          "WRITE_SIZE counters scale the traffic figures) and exit")
     args = ap.parse_args()
+    upg = args.workload == "upg"
+    if args.levels is None:
+        args.levels = 3 if upg else 6
+    if args.r is None:
+        args.r = 6 if upg else 12
+    if args.tol is None:
+        args.tol = 1e-8 if upg else 1e-10
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is described "
               f"in DESIGN.md and not built", file=sys.stderr)
@@ -242,6 +295,49 @@ def main():
         }
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline(args)
+    elif upg:
+        ch = C.upg(args.upg_n, seed=0)
+        rp, ci, v = B.device_csr(ch)
+        x = torch.empty(ch.n, dtype=torch.float64, device="cuda")
+        opts = B.default_options(levels=args.levels, precision=prec, profile=1)
+        sizes = []
+
+        def step():
+            h = B.Hierarchy(ch.n, rp, ci, v, (0, 0, 0), args.r, opts)
+            info = h.solve(x, args.tol, 200)
+            st = h.stats()
+            if not sizes:
+                sizes.extend((h.level_info(l).n, h.level_info(l).cr_rounds) for l in range(st.n_levels))
+            h.close()
+            return info, st
+
+        sec, res = _timed(step, args)
+        infos = [a for a, _ in res]
+        stats = [b for _, b in res]
+        sweep_ms, roof = _roofline(stats, None)
+        roof["kernel"] += ", R=%d" % args.r
+        gj_ms = sum(s.dense_update_ms for s in stats)
+        sweep_tot = sum(s.sweep_ms for s in stats)
+        if gj_ms > sweep_tot:
+            # the dense coarsest inverse dominates: report its rank-64 updates
+            roof = _roofline_dense(stats)
+        detail = _kernel_detail(stats)
+        detail.update({"cycles": [i.cycles for i in infos], "residual_l1": max(i.residual_l1 for i in infos),
+                       "converged": all(i.converged for i in infos),
+                       "l1_error_vs_closed_form": float(np.abs(x.cpu().numpy() - ch.exact).sum()),
+                       "level_sizes": [a for a, _ in sizes], "cr_rounds": [b for _, b in sizes]})
+        out = {
+            "metric": "setup+solve seconds to ||Bx||_1/||x||_1<=tol on an unstructured planar graph",
+            "value": round(sec, 6), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(sec * 1e3, 3), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if prec == B.FP64 else "f32+f64", "data": "synthetic",
+            "config": {"workload": f"unstructured planar graph: Delaunay of N={args.upg_n} random points "
+                                   f"(nnz={ch.nnz:,}), compatible-relaxation coarsening, r={args.r}, "
+                                   f"{args.levels} levels, tol {args.tol:g}", "precision": args.precision},
+            "roofline": roof, "detail": detail,
+        }
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline_upg(ch, args)
     elif args.workload == "learned":
         from paper_1004_1451_amd import learned as LRN
         t0 = time.perf_counter()

@@ -189,6 +189,12 @@ typedef struct {
     double tune_ms;         /* process total spent timing sweep candidates    */
     int64_t mlp_points;     /* learned form: F points judged (all levels)      */
     int64_t mlp_fallback;   /* of which fell back to the least-squares row     */
+    /* with options.profile: the rank-64 updates of the dense coarsest inverse
+       (coarsest levels without block structure): HIP-event time, launches,
+       and their flops (2 nb (m - nb)^2 each, m = n_L - 1)                */
+    double dense_update_ms;
+    int32_t dense_update_launches;
+    double dense_update_flops;
 } bamg_stats;
 
 typedef struct {

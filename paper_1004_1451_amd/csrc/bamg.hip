@@ -324,6 +324,7 @@ struct Engine : bamg_ctx {
     // compatible-relaxation work arrays (level-0 sized)
     int *cr_st = nullptr, *cr_isc = nullptr, *cr_cand = nullptr, *cr_pos = nullptr, *cr_flag = nullptr;
     double *cr_u0 = nullptr, *cr_ua = nullptr, *cr_ub = nullptr, *cr_part = nullptr, *cr_out = nullptr;
+    Csr<T> Wt;                       // M P of the Galerkin products without a grid
     // finest level in FP64 for the outer iteration
     int* b0rp = nullptr;
     int* b0ci = nullptr;
@@ -378,13 +379,14 @@ struct Engine : bamg_ctx {
     double* learn_acc = nullptr;
     int learn_grid = 0;
     // profiling
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_sweep, ev_gal, ev_ls;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_sweep, ev_gal, ev_ls, ev_gj;
+    double gj_flops = 0;             // flops of the profiled dense updates
 
     ~Engine() override {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cap_s) (void)hipStreamDestroy(cap_s);
-        for (auto* v : {&ev_sweep, &ev_gal, &ev_ls})
+        for (auto* v : {&ev_sweep, &ev_gal, &ev_ls, &ev_gj})
             for (auto& p : *v) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
         A.release();
     }
@@ -611,6 +613,7 @@ struct Engine : bamg_ctx {
             for (double** p : {&cr_u0, &cr_ua, &cr_ub}) *p = A.alloc<double>(n);
             cr_part = A.alloc<double>(2 * (size_t)CR_RED_BLOCKS);
             cr_out = A.alloc<double>(2);
+            Wt.rp = A.alloc<int>(n + 1);
         }
     }
 
@@ -1021,7 +1024,13 @@ struct Engine : bamg_ctx {
             int nb = std::min(GJ_NB, m - k0);
             LAUNCH(k_gj_diag, 1, BAMG_BLK, s, nL, k0, nb, Wp, (const double*)scale, minpiv);
             LAUNCH(k_gj_rowpanel, tiles, BAMG_BLK, s, m, nL, k0, nb, Wp);
+            std::pair<hipEvent_t, hipEvent_t> ev;
+            if (o.profile) ev = ev_begin();
             LAUNCH(k_gj_update, ut * ut, BAMG_BLK, s, m, nL, k0, nb, Wp);
+            if (o.profile) {
+                ev_end(ev, ev_gj);
+                gj_flops += 2.0 * nb * (double)(m - nb) * (double)(m - nb);
+            }
             LAUNCH(k_gj_colpanel, tiles, BAMG_BLK, s, m, nL, k0, nb, Wp);
         }
     }
@@ -1341,36 +1350,49 @@ struct Engine : bamg_ctx {
                lv.qvv);
     }
 
-    // B_{l+1} = Q (B P), T_{l+1} = Q (T P) for a level without a grid: count,
-    // scan, (re)allocate when the product outgrew its arrays, fill.
+    // One row-wise product C = L R (R ELL-4 when !rcsr, else CSR) into Cm:
+    // count, scan, (re)allocate when it outgrew its arrays, fill.  Returns
+    // whether Cm's arrays moved.
+    template <bool RCSR>
+    bool rowprod(int rows, int ncols, const int* lrp, const int* lci, const T* lv, const int* rrp, const int* rci,
+                 const T* rv, int* cnt, Csr<T>& Cm, const char* what) {
+        zero(err, sizeof(int) * 4);
+        LAUNCH((k_rowprod<T, RCSR>), rows, BAMG_WAVE, s, rows, ncols, 0, lrp, lci, lv, rrp, rci, rv, cnt,
+               (const int*)nullptr, (int*)nullptr, (T*)nullptr, err);
+        scan(rows, cnt, Cm.rp);
+        const int tot = get1(Cm.rp + rows);
+        if (get1(err) & ERR_GALCAP)
+            fail(BAMG_EUNSUPPORTED, "a row of %s needs more than %d products", what, RP_CAP);
+        bool moved = false;
+        if (tot > Cm.cap) {
+            Cm.cap = tot + tot / 4;
+            Cm.ci = A.alloc<int>(Cm.cap);
+            Cm.v = A.alloc<T>(Cm.cap);
+            moved = true;
+        }
+        LAUNCH((k_rowprod<T, RCSR>), rows, BAMG_WAVE, s, rows, ncols, 1, lrp, lci, lv, rrp, rci, rv, cnt,
+               (const int*)Cm.rp, Cm.ci, Cm.v, err);
+        return moved;
+    }
+
+    // B_{l+1} = Q (B P), T_{l+1} = Q (T P) for a level without a grid, each
+    // as W = M P, then Q W (T_0 = I: Q P).
     void galerkin_u(int l, bool profile) {
         auto& f = L[l];
         auto& c = L[l + 1];
-        const int nc = c.rows;
+        const int nc = c.rows, nl = f.cont_rows;
         bool moved = false;
         for (int which = 0; which < 2; ++which) {
             Csr<T>& M = which == 0 ? f.B : f.Tm;
             Csr<T>& Cm = which == 0 ? c.B : c.Tm;
-            zero(err, sizeof(int) * 4);
-            LAUNCH((k_ugal<T>), nc, BAMG_WAVE, s, nc, 0, (const int*)f.qrp, (const int*)f.qci, (const T*)f.qvv,
-                   (const int*)M.rp, (const int*)M.ci, (const T*)M.v, (const int*)f.pc, (const T*)f.pv, f.cnt,
-                   (const int*)nullptr, (int*)nullptr, (T*)nullptr, err);
-            scan(nc, f.cnt, Cm.rp);
-            const int tot = get1(Cm.rp + nc);
-            if (get1(err) & ERR_GALCAP)
-                fail(BAMG_EUNSUPPORTED, "a row of the level-%d Galerkin product needs more than %d products", l + 1,
-                     UG_CAP);
-            if (tot > Cm.cap) {
-                Cm.cap = tot + tot / 4;
-                Cm.ci = A.alloc<int>(Cm.cap);
-                Cm.v = A.alloc<T>(Cm.cap);
-                moved = true;
-            }
             std::pair<hipEvent_t, hipEvent_t> ev;
             if (profile) ev = ev_begin();
-            LAUNCH((k_ugal<T>), nc, BAMG_WAVE, s, nc, 1, (const int*)f.qrp, (const int*)f.qci, (const T*)f.qvv,
-                   (const int*)M.rp, (const int*)M.ci, (const T*)M.v, (const int*)f.pc, (const T*)f.pv, f.cnt,
-                   (const int*)Cm.rp, Cm.ci, Cm.v, err);
+            if (M.rp) {
+                rowprod<false>(nl, nc, M.rp, M.ci, M.v, nullptr, f.pc, f.pv, itmp, Wt, "M P");
+                moved |= rowprod<true>(nc, nc, f.qrp, f.qci, f.qvv, Wt.rp, Wt.ci, Wt.v, f.cnt, Cm, "Q (M P)");
+            } else {
+                moved |= rowprod<false>(nc, nc, f.qrp, f.qci, f.qvv, nullptr, f.pc, f.pv, f.cnt, Cm, "Q P");
+            }
             if (profile) ev_end(ev, ev_gal);
         }
         zero(err, sizeof(int) * 4);
@@ -1508,6 +1530,9 @@ struct Engine : bamg_ctx {
         }
         acc(ev_gal, st.galerkin_ms, st.galerkin_launches);
         acc(ev_ls, st.lsfit_ms, st.lsfit_launches);
+        acc(ev_gj, st.dense_update_ms, st.dense_update_launches);
+        st.dense_update_flops = gj_flops;
+        gj_flops = 0;
         // algorithmic bytes of one level-0 launch
         const long long n0 = L[0].cont_rows;
         const int vb = sizeof(T);

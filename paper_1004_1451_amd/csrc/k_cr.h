@@ -17,7 +17,7 @@ enum : int {
     ERR_UNSYM = 32,       // pattern of B not symmetric
     ERR_NOCOARSE = 64,    // an F point without a coarse neighbour
     ERR_WIDEN = 128,      // more candidates than LSU_K
-    ERR_GALCAP = 256,     // a coarse row needs more than UG_CAP products
+    ERR_GALCAP = 256,     // a product row needs more than RP_CAP terms
 };
 
 enum : int { MIS_UND = 0, MIS_IN = 1, MIS_OUT = 2 };
@@ -385,46 +385,49 @@ __global__ void k_qu_finish(int nc, const int* __restrict__ qrp, int* __restrict
 }
 
 // ---------------------------------------------------------------- Galerkin
-// C = Q (M P) for general sparsity, one wavefront per coarse row I.  The
-// products q_Ia m_ik p_kJ are enumerated in the loop order (Q entry a, M entry
-// of row i = qci[a], P slot of row k), each tagged with its position; sorting
-// the keys (J << UG_POSB) | position groups equal columns with the positions
-// in loop order, and each column's value is summed in that order: the inner
-// sum over k of m_ik p_kJ per Q entry, times q_Ia, added over a (the order of
-// Q (M P)).  M = nullptr rows: M = I.  Pass 0 counts the columns of each row
-// into cnt; pass 1 writes the row at rp[I].
-#define UG_CAP 2048
-#define UG_POSB 11
-#define UG_MAXQ 512
+// Row-wise sparse product C = L R, one wavefront per row I of L (CSR, values
+// lv; lv = nullptr: all ones).  R is ELL-4 (RCSR = false: rci/rv are the
+// 4-slot columns/values of P, -1 = empty) or CSR (rrp, rci, rv).  The
+// products l_Ia r_{i_a J} are enumerated in loop order (entry a of row I,
+// then the entries of row i_a of R) and tagged with their position; sorting
+// the keys (J << RP_POSB) | position groups equal columns with the positions
+// in loop order, so each value is summed over a in the order of L's row, as
+// a sequential row-times-matrix product does.  The Galerkin products are
+// B_{l+1} = Q (B P) and T_{l+1} = Q (T P), each as W = M P, then Q W (the
+// order of the plain definition; M = I needs only Q P).  Pass 0 counts the
+// columns of each row into cnt; pass 1 writes the row at rp[I].
+#define RP_CAP 4096
+#define RP_POSB 12
+#define RP_MAXL 1024
 
-template <typename MV>
+template <typename MV, bool RCSR>
 __global__ void __launch_bounds__(BAMG_WAVE)
-k_ugal(int nc, int pass, const int* __restrict__ qrp, const int* __restrict__ qci, const MV* __restrict__ qv,
-       const int* __restrict__ mrp, const int* __restrict__ mci, const MV* __restrict__ mv,
-       const int* __restrict__ pc, const MV* __restrict__ pv, int* __restrict__ cnt, const int* __restrict__ rp,
-       int* __restrict__ ci, MV* __restrict__ cv, int* __restrict__ err) {
-    __shared__ unsigned key[UG_CAP];
-    __shared__ double val[UG_CAP];
-    __shared__ unsigned short qa[UG_CAP];
-    __shared__ int off[UG_MAXQ + 1];
-    __shared__ int ustart[UG_CAP + 1];
+k_rowprod(int nrows, int ncols, int pass, const int* __restrict__ lrp, const int* __restrict__ lci,
+          const MV* __restrict__ lv, const int* __restrict__ rrp, const int* __restrict__ rci,
+          const MV* __restrict__ rv, int* __restrict__ cnt, const int* __restrict__ rp, int* __restrict__ ci,
+          MV* __restrict__ cv, int* __restrict__ err) {
+    __shared__ unsigned key[RP_CAP];
+    __shared__ int tix[RP_CAP];
+    __shared__ unsigned short la[RP_CAP];
+    __shared__ int off[RP_MAXL + 1];
+    __shared__ int ustart[RP_CAP + 1];
     const int I = blockIdx.x;
     const int lane = threadIdx.x;
-    if (I >= nc) return;
-    const int q0 = qrp[I], nq = qrp[I + 1] - q0;
-    if (nq > UG_MAXQ) {
+    if (I >= nrows) return;
+    const int q0 = lrp[I], nq = lrp[I + 1] - q0;
+    if (nq > RP_MAXL || ncols >= (1 << (32 - RP_POSB))) {
         if (lane == 0) { atomicOr(err, ERR_GALCAP); if (pass == 0) cnt[I] = 0; }
         return;
     }
-    // products per Q entry, then their offsets
+    // products per entry of L's row, then their offsets
     for (int a = lane; a < nq; a += BAMG_WAVE) {
-        const int i = qci[q0 + a];
+        const int i = lci[q0 + a];
         int c = 0;
-        const int k0 = mrp ? mrp[i] : i, k1 = mrp ? mrp[i + 1] : i + 1;
-        for (int p = k0; p < k1; ++p) {
-            const int k = mrp ? mci[p] : i;
+        if (RCSR) {
+            c = rrp[i + 1] - rrp[i];
+        } else {
 #pragma unroll
-            for (int s = 0; s < 4; ++s) c += pc[(size_t)k * 4 + s] >= 0;
+            for (int s = 0; s < 4; ++s) c += rci[(size_t)i * 4 + s] >= 0;
         }
         off[a + 1] = c;
     }
@@ -435,26 +438,21 @@ k_ugal(int nc, int pass, const int* __restrict__ qrp, const int* __restrict__ qc
     }
     __syncthreads();
     const int tot = off[nq];
-    if (tot > UG_CAP || nc >= (1 << (32 - UG_POSB))) {
+    if (tot > RP_CAP) {
         if (lane == 0) { atomicOr(err, ERR_GALCAP); if (pass == 0) cnt[I] = 0; }
         return;
     }
     for (int a = lane; a < nq; a += BAMG_WAVE) {
-        const int i = qci[q0 + a];
+        const int i = lci[q0 + a];
         int pos = off[a];
-        const int k0 = mrp ? mrp[i] : i, k1 = mrp ? mrp[i + 1] : i + 1;
-        for (int p = k0; p < k1; ++p) {
-            const int k = mrp ? mci[p] : i;
-            const double m = mrp ? (double)mv[p] : 1.0;
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int J = pc[(size_t)k * 4 + s];
-                if (J < 0) continue;
-                key[pos] = ((unsigned)J << UG_POSB) | (unsigned)pos;
-                val[pos] = m * (double)pv[(size_t)k * 4 + s];
-                qa[pos] = (unsigned short)a;
-                ++pos;
-            }
+        const int t0 = RCSR ? rrp[i] : i * 4, t1 = RCSR ? rrp[i + 1] : i * 4 + 4;
+        for (int t = t0; t < t1; ++t) {
+            const int J = rci[t];
+            if (J < 0) continue;
+            key[pos] = ((unsigned)J << RP_POSB) | (unsigned)pos;
+            tix[pos] = t;
+            la[pos] = (unsigned short)a;
+            ++pos;
         }
     }
     // bitonic sort of the keys, padded to a power of two
@@ -480,7 +478,7 @@ k_ugal(int nc, int pass, const int* __restrict__ qrp, const int* __restrict__ qc
     for (int base = 0; base < tot; base += BAMG_WAVE) {
         const int t = base + lane;
         bool first = false;
-        if (t < tot) first = t == 0 || (key[t] >> UG_POSB) != (key[t - 1] >> UG_POSB);
+        if (t < tot) first = t == 0 || (key[t] >> RP_POSB) != (key[t - 1] >> RP_POSB);
         const unsigned long long mask = __ballot(first);
         const int rank = nu + __popcll(mask & ((1ull << lane) - 1ull));
         if (first) ustart[rank] = t;
@@ -496,21 +494,14 @@ k_ugal(int nc, int pass, const int* __restrict__ qrp, const int* __restrict__ qc
     const int o = rp[I];
     for (int u = lane; u < nu; u += BAMG_WAVE) {
         const int t0 = ustart[u], t1 = ustart[u + 1];
-        double outer = 0.0, inner = 0.0;
-        int cura = -1;
+        double sum = 0.0;
         for (int t = t0; t < t1; ++t) {
-            const int pos = (int)(key[t] & ((1u << UG_POSB) - 1u));
-            const int a = qa[pos];
-            if (a != cura) {
-                if (cura >= 0) outer += (double)qv[q0 + cura] * inner;
-                cura = a;
-                inner = 0.0;
-            }
-            inner += val[pos];
+            const int pos = (int)(key[t] & ((1u << RP_POSB) - 1u));
+            const double l = lv ? (double)lv[q0 + la[pos]] : 1.0;
+            sum += l * (double)rv[tix[pos]];
         }
-        outer += (double)qv[q0 + cura] * inner;
-        ci[o + u] = (int)(key[t0] >> UG_POSB);
-        cv[o + u] = (MV)outer;
+        ci[o + u] = (int)(key[t0] >> RP_POSB);
+        cv[o + u] = (MV)sum;
     }
 }
 

@@ -137,55 +137,64 @@ k_gj_rowpanel(int m, int ld, int k0, int nb, double* __restrict__ A) {
 }
 
 // Rank-nb update of every entry outside row block and column block k:
-// A[i, j] -= A[i, k-block] * A[k-block, j].  128 x 128 output tiles, 8 x 8
-// per thread (256 threads), the k-block factors staged in LDS (A part
-// transposed so that both operands are read as contiguous 8-double runs).
-// Rows / columns inside the k-block are computed but not written.
-#define GJ_T 128
+// A[i, j] -= A[i, k-block] * A[k-block, j].  64 x 64 output tiles aligned with
+// the 64-row blocks (a tile in the k row or column block has nothing to do),
+// 4 x 4 per thread (256 threads); the k-block factors are staged in LDS in two
+// halves of 32 (A part transposed so that both operands are read as
+// contiguous 4-double runs).  34 KB of LDS lets four workgroups share a CU, so
+// one workgroup's read-modify-write of its tile overlaps the others' products.
+// The sum over k runs in order 0 .. nb-1.
+#define GJ_T 64
+#define GJ_KH 32
 __global__ void __launch_bounds__(BAMG_BLK)
 k_gj_update(int m, int ld, int k0, int nb, double* __restrict__ A) {
-    __shared__ double AsT[GJ_NB][GJ_T + 2];
-    __shared__ double Bs[GJ_NB][GJ_T + 2];
+    __shared__ double AsT[GJ_KH][GJ_T + 2];
+    __shared__ double Bs[GJ_KH][GJ_T + 2];
     const int tiles = ceil_div(m, GJ_T);
-    int t = xcd_tile(blockIdx.x, gridDim.x);
-    int ti = t / tiles, tj = t % tiles;
-    int i0 = ti * GJ_T, j0 = tj * GJ_T;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int ti = t / tiles, tj = t % tiles;
+    const int i0 = ti * GJ_T, j0 = tj * GJ_T;
+    if (i0 == k0 || j0 == k0) return;         // inside the k row / column block
     const int tid = threadIdx.x;
-    // A[i0 + r][k0 + c]  -> AsT[c][r];  A[k0 + r][j0 + c] -> Bs[r][c]
-    for (int e = tid; e < GJ_T * GJ_NB; e += BAMG_BLK) {
-        int r = e / GJ_NB, c = e % GJ_NB;
-        AsT[c][r] = (i0 + r < m && c < nb) ? A[(size_t)(i0 + r) * ld + k0 + c] : 0.0;
+    const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0;
+    for (int kh = 0; kh < nb; kh += GJ_KH) {
+        // A[i0 + r][k0 + kh + c] -> AsT[c][r];  A[k0 + kh + r][j0 + c] -> Bs[r][c]
+        for (int e = tid; e < GJ_T * GJ_KH; e += BAMG_BLK) {
+            const int r = e / GJ_KH, c = e % GJ_KH;
+            AsT[c][r] = (i0 + r < m && kh + c < nb) ? A[(size_t)(i0 + r) * ld + k0 + kh + c] : 0.0;
+        }
+        for (int e = tid; e < GJ_KH * GJ_T; e += BAMG_BLK) {
+            const int r = e / GJ_T, c = e % GJ_T;
+            Bs[r][c] = (j0 + c < m && kh + r < nb) ? A[(size_t)(k0 + kh + r) * ld + j0 + c] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int k = 0; k < GJ_KH; ++k) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = AsT[k][tr + a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bv[b] = Bs[k][tc + b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+        }
+        __syncthreads();
     }
-    for (int e = tid; e < GJ_NB * GJ_T; e += BAMG_BLK) {
-        int r = e / GJ_T, c = e % GJ_T;
-        Bs[r][c] = (j0 + c < m && r < nb) ? A[(size_t)(k0 + r) * ld + j0 + c] : 0.0;
-    }
-    __syncthreads();
-    const int tr = (tid / 16) * 8, tc = (tid % 16) * 8;
-    double acc[8][8];
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+    for (int a = 0; a < 4; ++a) {
+        const int i = i0 + tr + a;
+        if (i >= m) continue;
 #pragma unroll
-        for (int b = 0; b < 8; ++b) acc[a][b] = 0;
-    for (int k = 0; k < nb; ++k) {
-        double av[8], bv[8];
-#pragma unroll
-        for (int a = 0; a < 8; ++a) av[a] = AsT[k][tr + a];
-#pragma unroll
-        for (int b = 0; b < 8; ++b) bv[b] = Bs[k][tc + b];
-#pragma unroll
-        for (int a = 0; a < 8; ++a)
-#pragma unroll
-            for (int b = 0; b < 8; ++b) acc[a][b] += av[a] * bv[b];
-    }
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-        int i = i0 + tr + a;
-        if (i >= m || (i >= k0 && i < k0 + nb)) continue;
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            int j = j0 + tc + b;
-            if (j < m && !(j >= k0 && j < k0 + nb)) A[(size_t)i * ld + j] -= acc[a][b];
+        for (int b = 0; b < 4; ++b) {
+            const int j = j0 + tc + b;
+            if (j < m) A[(size_t)i * ld + j] -= acc[a][b];
         }
     }
 }

@@ -161,6 +161,19 @@ def test_cr_stationary_matches_closed_form_and_oracle(name, N, seed):
     assert [h.level_info(l).n for l in range(3)] == [lv.B.shape[0] for lv in ho.levels]
 
 
+def test_cr_dense_coarsest_inverse_at_1234_points():
+    # the coarsest level without a grid takes the dense Gauss-Jordan inverse:
+    # 20 blocks of 64 (the last one partial) against the SVD pseudo-inverse
+    ch = C.upg(16384, seed=0)
+    h = B.Hierarchy.from_chain(ch, 6, B.default_options(levels=3, stop_after=2))
+    BL = _csr(h, 2, "B").toarray()
+    nL = BL.shape[0]
+    assert nL > 1200
+    W = h.export(2, B.X_W).reshape(nL, nL)
+    Wo = O.coarsest_pinv(BL)
+    assert np.abs(W - Wo).max() <= 1e-8 * np.abs(Wo).max()
+
+
 def test_cr_mixed_precision_converges():
     ch = C.upg(2048, seed=0)
     x, info, h = B.stationary(ch, 6, tol=1e-10, max_cycles=200, levels=3, precision=B.MIXED)
