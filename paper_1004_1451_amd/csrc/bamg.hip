@@ -341,9 +341,9 @@ struct Engine : bamg_ctx {
            *t2 = nullptr, *rre = nullptr, *rim = nullptr, *gtpart = nullptr;
     float* Wfp = nullptr;
     double *scale = nullptr, *minpiv = nullptr, *cy = nullptr, *csc = nullptr, *dots = nullptr;
-    double *Vb = nullptr, *Hh = nullptr, *Hrow = nullptr, *sel_lam = nullptr, *sel_s = nullptr;
+    double *Vb = nullptr, *Hh = nullptr, *sel_lam = nullptr, *sel_s = nullptr;
     int* nsel = nullptr;
-    int HS = 1, HRS = 1, SS = 1, DS = 1;
+    int HS = 1, SS = 1, DS = 1;
     bool dense_fallback = false;
     // eigen tables
     double* lam = nullptr;
@@ -365,7 +365,6 @@ struct Engine : bamg_ctx {
            *ysol = nullptr, *hbuf = nullptr, *rvec = nullptr, *est = nullptr, *xperm = nullptr;
     int *act = nullptr, *kd = nullptr;
     int* cmask = nullptr;            // chains the cycle works on (nch > 1; all ones outside solve)
-    double* hrow = nullptr;          // preconditioned Arnoldi: Hessenberg scratch per chain
     int* hfail = nullptr;
     double *vin = nullptr, *vout = nullptr;   // permuted vectors of bamg_apply_vcycle
     // graph of one cycle on fixed buffers
@@ -670,12 +669,10 @@ struct Engine : bamg_ctx {
         csc = A.alloc<double>((size_t)nch * SCS);
         const int am = std::max(1, AMmax);
         HS = (am + 1) * am;
-        HRS = am * am;
         SS = 16 * 2 * am;
         DS = am + 2;
         Vb = A.alloc<double>(std::max<long long>(aoff, 1));
         Hh = A.alloc<double>((size_t)nch * HS);
-        Hrow = A.alloc<double>((size_t)nch * HRS);
         sel_lam = A.alloc<double>((size_t)nch * LSS);
         sel_s = A.alloc<double>((size_t)nch * SS);
         nsel = A.alloc<int>((size_t)nch * NS);
@@ -1075,8 +1072,8 @@ struct Engine : bamg_ctx {
                 project_and_normalize(j);
             }
         }
-        LAUNCH(k_cz_hess, nch, BAMG_WAVE, s, (const CoarseDesc*)cd, want, (const double*)Hh, HS, Hrow, HRS, nsel, NS,
-               sel_lam, LSS, sel_s, SS);
+        LAUNCH(k_cz_hess, nch, BAMG_WAVE, s, (const CoarseDesc*)cd, want, (const double*)Hh, HS, nsel, NS, sel_lam,
+               LSS, sel_s, SS);
         std::vector<int> hs = getn(nsel, (size_t)nch * NS);
         int emax = 0;
         for (int c = 0; c < nch; ++c) {
@@ -1733,10 +1730,7 @@ struct Engine : bamg_ctx {
         const int ld = m + 1, HSg = (m + 1) * m, GS = m + 2;
         const int nb = nblk(N);
         const ChainGeo* g0 = L[0].dgeo;
-        if (!hrow) {
-            hrow = A.alloc<double>((size_t)nch * HQR_MAXM * HQR_MAXM);
-            hfail = A.alloc<int>(nch);
-        }
+        if (!hfail) hfail = A.alloc<int>(nch);
         std::vector<int> hact(nch, 1), hkd(nch, 0), done(nch, 0);
         auto residuals = [&](std::vector<double>& rel, std::vector<double>& nu) {
             LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)xi, -1.0, rvec,
@@ -1789,8 +1783,8 @@ struct Engine : bamg_ctx {
                 LAUNCH(k_arn_step, ceil_div(nch, 64), 64, s, nch, j, ld, (const int*)act, (const double*)hbuf2,
                        (const double*)hbuf, GS, Hg, HSg, gsaux, GS, gscoef, sc + 6, SCS);
                 // Ritz vector of the eigenvalue of H_{j+1} closest to 0
-                LAUNCH(k_hess_near0, nch, BAMG_WAVE, s, j + 1, (const int*)act, (const double*)Hg, HSg, ld, hrow,
-                       ysol, GS, hfail);
+                LAUNCH(k_hess_near0, nch, BAMG_WAVE, s, j + 1, (const int*)act, (const double*)Hg, HSg, ld, ysol, GS,
+                       hfail);
                 for (int c = 0; c < nch; ++c) hkd[c] = j + 1;
                 HIPCHK(hipMemcpyAsync(kd, hkd.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
                 LAUNCH(k_seg_ritz, nb, BAMG_BLK, s, N, g0, nch, (const int*)act, (const int*)kd, (const double*)Vk,

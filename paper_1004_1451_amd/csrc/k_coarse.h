@@ -964,26 +964,24 @@ __global__ void k_cz_tables(int nch, const int* __restrict__ nsel, int NS, const
 // the leading k x k block of its Arnoldi matrix (hessenberg_near_zero_body).
 __global__ void __launch_bounds__(BAMG_WAVE)
 k_hess_near0(int k, const int* __restrict__ act, const double* __restrict__ Hall, int HS, int ld,
-             double* __restrict__ Hrow, double* __restrict__ eta, int ES, int* __restrict__ fail) {
+             double* __restrict__ eta, int ES, int* __restrict__ fail) {
     const int c = blockIdx.x;
     if (!act[c]) return;
-    hessenberg_near_zero_body(k, Hall + (size_t)c * HS, ld, Hrow + (size_t)c * HQR_MAXM * HQR_MAXM,
-                              eta + (size_t)c * ES, fail + c);
+    hessenberg_near_zero_body(k, Hall + (size_t)c * HS, ld, eta + (size_t)c * ES, fail + c);
 }
 
 // One wavefront per chain: eigenvalues of its Arnoldi Hessenberg matrix
 // (stride HS), selection and eigenvectors (see hessenberg_eig_body).
 // Chains without eigenpairs report no selection.
 __global__ void __launch_bounds__(BAMG_WAVE)
-k_cz_hess(const CoarseDesc* __restrict__ cd, int want, const double* __restrict__ Hh, int HS, double* __restrict__ Hrow,
-          int HRS, int* __restrict__ nsel, int NS, double* __restrict__ sel_lam, int LS, double* __restrict__ sel_s,
-          int SS) {
+k_cz_hess(const CoarseDesc* __restrict__ cd, int want, const double* __restrict__ Hh, int HS,
+          int* __restrict__ nsel, int NS, double* __restrict__ sel_lam, int LS, double* __restrict__ sel_s, int SS) {
     const int c = blockIdx.x;
     const CoarseDesc d = cd[c];
     if (d.am < 1 || want < 1) {
         if (threadIdx.x == 0) { nsel[(size_t)c * NS] = 0; nsel[(size_t)c * NS + 1] = 0; nsel[(size_t)c * NS + 2] = 0; }
         return;
     }
-    hessenberg_eig_body(d.am, want, Hh + (size_t)c * HS, Hrow + (size_t)c * HRS, nsel + (size_t)c * NS,
-                        sel_lam + (size_t)c * LS, sel_s + (size_t)c * SS);
+    hessenberg_eig_body(d.am, want, Hh + (size_t)c * HS, nsel + (size_t)c * NS, sel_lam + (size_t)c * LS,
+                        sel_s + (size_t)c * SS);
 }

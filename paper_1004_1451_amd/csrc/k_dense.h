@@ -684,7 +684,7 @@ __device__ void hqr_wave(int m, double* A, double* wr, double* wi, int* fail) {
 // Packed upper triangle (complex): row k, column j >= k.
 __device__ __forceinline__ int upk(int m, int k, int j) { return k * m - (k * (k - 1)) / 2 + (j - k); }
 
-// z <- (H - theta I)^-1 z for the Hessenberg H (global, row-major m x m),
+// z <- (H - theta I)^-1 z for the Hessenberg H (LDS, row-major m x m),
 // one wavefront; U (LDS, packed, 2 doubles per entry), z (LDS, complex).
 __device__ void hess_shift_solve_wave(int m, const double* __restrict__ H, double thr, double thi,
                                       double* U, double* zr, double* zi, double hnorm) {
@@ -772,11 +772,12 @@ __device__ void hess_shift_solve_wave(int m, const double* __restrict__ H, doubl
 //   nsel_out[0] = selected entries, [1] = real columns they need, [2] = fail;
 //   sel_lam[2e..2e+1] = lam of entry e (Im >= 0 member of a pair);
 //   sel_s[e*2m + 2j..] = (re, im) of the eigenvector of H for entry e.
-// Hrow: scratch m*m doubles (row-major copy of H_m).
-__device__ void hessenberg_eig_body(int m, int want, const double* __restrict__ Hh, double* __restrict__ Hrow,
-                                    int* __restrict__ nsel_out, double* __restrict__ sel_lam,
-                                    double* __restrict__ sel_s) {
+// A row-major copy of H_m stays in LDS for the inverse iterations, whose
+// elimination reads one row per step.
+__device__ void hessenberg_eig_body(int m, int want, const double* __restrict__ Hh, int* __restrict__ nsel_out,
+                                    double* __restrict__ sel_lam, double* __restrict__ sel_s) {
     __shared__ double A[HQR_MAXM * HQR_LD];
+    __shared__ double Hs[HQR_MAXM * HQR_MAXM];
     __shared__ double wr[HQR_MAXM], wi[HQR_MAXM], zr[HQR_MAXM], zi[HQR_MAXM];
     __shared__ int used[HQR_MAXM];
     __shared__ int fail;
@@ -786,7 +787,7 @@ __device__ void hessenberg_eig_body(int m, int want, const double* __restrict__ 
     for (int i = 0; i < m; ++i) {
         double v = 0;
         if (lane < m) v = (i <= lane + 1) ? Hh[(size_t)lane * (m + 1) + i] : 0.0;
-        if (lane < m) { A[i * HQR_LD + lane] = v; Hrow[(size_t)i * m + lane] = v; }
+        if (lane < m) { A[i * HQR_LD + lane] = v; Hs[i * m + lane] = v; }
         hn = fmax(hn, fabs(v));
     }
     // max over lanes
@@ -823,7 +824,7 @@ __device__ void hessenberg_eig_body(int m, int want, const double* __restrict__ 
         if (lane < m) { zr[lane] = 1.0; zi[lane] = 0.0; }
         lds_sync();
         for (int itn = 0; itn < 3; ++itn) {
-            hess_shift_solve_wave(m, Hrow, thr, thi, A, zr, zi, hn);
+            hess_shift_solve_wave(m, Hs, thr, thi, A, zr, zi, hn);
             double s = lane < m ? zr[lane] * zr[lane] + zi[lane] * zi[lane] : 0.0;
             s = wave_sum(s);
             s = __shfl(s, 0, BAMG_WAVE);
@@ -853,11 +854,13 @@ __device__ void hessenberg_eig_body(int m, int want, const double* __restrict__ 
 // matrix H (column-major, leading dimension ld) closest to 0 and its
 // eigenvector by three steps of inverse iteration with (H - theta I),
 // normalised to ||eta||_2 = 1 with its largest-modulus entry (lowest index on
-// ties) real and positive; the real part goes to eta[0..k-1].  Hrow: scratch
-// of k * k doubles (row-major copy).  *fail = 1 when the QR iteration fails.
-__device__ void hessenberg_near_zero_body(int k, const double* __restrict__ Hh, int ld, double* __restrict__ Hrow,
-                                          double* __restrict__ eta, int* __restrict__ fail_out) {
+// ties) real and positive; the real part goes to eta[0..k-1].  A row-major
+// copy of the block stays in LDS for the inverse iterations.  *fail = 1 when
+// the QR iteration fails.
+__device__ void hessenberg_near_zero_body(int k, const double* __restrict__ Hh, int ld, double* __restrict__ eta,
+                                          int* __restrict__ fail_out) {
     __shared__ double A[HQR_MAXM * HQR_LD];
+    __shared__ double Hs[HQR_MAXM * HQR_MAXM];
     __shared__ double wr[HQR_MAXM], wi[HQR_MAXM], zr[HQR_MAXM], zi[HQR_MAXM];
     __shared__ int fail;
     const int lane = threadIdx.x;
@@ -866,7 +869,7 @@ __device__ void hessenberg_near_zero_body(int k, const double* __restrict__ Hh, 
     for (int i = 0; i < k; ++i) {
         double v = 0;
         if (lane < k) v = (i <= lane + 1) ? Hh[(size_t)lane * ld + i] : 0.0;
-        if (lane < k) { A[i * HQR_LD + lane] = v; Hrow[(size_t)i * k + lane] = v; }
+        if (lane < k) { A[i * HQR_LD + lane] = v; Hs[i * k + lane] = v; }
         hn = fmax(hn, fabs(v));
     }
 #pragma unroll
@@ -885,7 +888,7 @@ __device__ void hessenberg_near_zero_body(int k, const double* __restrict__ Hh, 
     if (lane < k) { zr[lane] = 1.0; zi[lane] = 0.0; }
     lds_sync();
     for (int itn = 0; itn < 3; ++itn) {
-        hess_shift_solve_wave(k, Hrow, thr, thi, A, zr, zi, hn);
+        hess_shift_solve_wave(k, Hs, thr, thi, A, zr, zi, hn);
         double s = lane < k ? zr[lane] * zr[lane] + zi[lane] * zi[lane] : 0.0;
         s = wave_sum(s);
         s = __shfl(s, 0, BAMG_WAVE);
