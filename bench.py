@@ -147,7 +147,9 @@ def _roofline(stats, traffic):
     st = stats[-1]
     return sweep_ms, {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                       "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                      "kernel": "k_sweep_v<VW=%d,BS=%d> (level-0 test-vector sweep)" % (st.sweep_vw, st.sweep_bs),
+                      "kernel": "%s<VW=%d,BS=%d> (level-0 test-vector sweep%s)" % (
+                          "k_sweep_ve" if st.sweep_ell else "k_sweep_v", st.sweep_vw, st.sweep_bs,
+                          ", ELL-4 copy of B_0" if st.sweep_ell else ""),
                       "bytes_per_launch": int(sweep_bytes), "mean_launch_us": round(sweep_ms * 1e3, 2)}
 
 
@@ -240,7 +242,10 @@ def main():
     from paper_1004_1451_amd import chains as C
 
     prec = B.FP64 if args.precision == "fp64" else B.MIXED
-    traffic = _traffic_from_profiles(f"k_sweep_v_{args.workload}_{args.precision}")
+    def traffic_of(stats):
+        # counters of the sweep form that ran (ELL-4 copy or CSR)
+        form = "k_sweep_ve" if stats[-1].sweep_ell else "k_sweep_v"
+        return _traffic_from_profiles(f"{form}_{args.workload}_{args.precision}")
     if args.workload == "tandem":
         ch = C.tandem_queue(args.N)
         rp, ci, v = B.device_csr(ch)
@@ -261,7 +266,7 @@ def main():
         sec, res = _timed(step, args)
         infos = [a for a, _ in res]
         stats = [b for _, b in res]
-        sweep_ms, roof = _roofline(stats, traffic if args.relax == "jacobi" else None)
+        sweep_ms, roof = _roofline(stats, traffic_of(stats) if args.relax == "jacobi" else None)
         roof["kernel"] += ", R=%d" % args.r
         if args.relax == "mcgs":
             roof["kernel"] = "k_mcgs_tv<VW=%d> x colours (level-0 test-vector Gauss-Seidel sweep), R=%d" % (
@@ -375,7 +380,7 @@ def main():
                 res[name]["fallback_fraction"] = round(st.mlp_fallback / max(1, st.mlp_points), 4)
             if name == "mixed_learned_1pass":
                 sec, stats = sec_f, [b for _, b in rr]
-        sweep_ms, roof = _roofline(stats, traffic if args.precision == "mixed" else None)
+        sweep_ms, roof = _roofline(stats, traffic_of(stats) if args.precision == "mixed" else None)
         roof["kernel"] += ", R=%d" % args.r
         out = {
             "metric": "setup+solve seconds to ||Bx||_1/||x||_1<=1e-10 at n=4.2M, learned + mixed form",
@@ -409,7 +414,7 @@ def main():
 
         sec, res = _timed(step, args)
         stats = [r[3] for r in res]
-        sweep_ms, roof = _roofline(stats, traffic)
+        sweep_ms, roof = _roofline(stats, traffic_of(stats))
         roof["kernel"] += ", R=%d, all 64 chains" % args.r
         detail = _kernel_detail(stats)
         detail.update({"chains_per_s": round(64 / sec, 2), "cycles": [r[0].cycles for r in res],

@@ -195,6 +195,9 @@ typedef struct {
     double dense_update_ms;
     int32_t dense_update_launches;
     double dense_update_flops;
+    int32_t sweep_ell;      /* 1: the level-0 sweeps, the cycle's level-0 residual
+                               and the outer SpMV read a 4-wide ELL copy of B_0
+                               (every row has at most 4 entries)            */
 } bamg_stats;
 
 typedef struct {

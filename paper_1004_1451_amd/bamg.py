@@ -76,7 +76,8 @@ class Stats(C.Structure):
                 ("cycle_graph", C.c_int32), ("cycle_host_us", C.c_double), ("cycle_gpu_us", C.c_double),
                 ("sweep_vw", C.c_int32), ("sweep_bs", C.c_int32), ("tune_ms", C.c_double),
                 ("mlp_points", C.c_int64), ("mlp_fallback", C.c_int64), ("dense_update_ms", C.c_double),
-                ("dense_update_launches", C.c_int32), ("dense_update_flops", C.c_double)]
+                ("dense_update_launches", C.c_int32), ("dense_update_flops", C.c_double),
+                ("sweep_ell", C.c_int32)]
 
 
 class MlpTrainOpts(C.Structure):

@@ -245,6 +245,8 @@ struct Csr {
     int* rp = nullptr;
     int* ci = nullptr;
     T* v = nullptr;
+    int* eci = nullptr;              // ELL-4 copy (rows of at most 4 entries), or null
+    T* ev = nullptr;
 };
 
 // Rows of one level: all present chains, continuing chains first.
@@ -329,6 +331,7 @@ struct Engine : bamg_ctx {
     int* b0rp = nullptr;
     int* b0ci = nullptr;
     double* b0v = nullptr;
+    double* b0ev = nullptr;          // FP64 values of the ELL-4 copy of B_0 (columns in L[0].B.eci)
     int nnz0 = 0;
     bool reordered = false;
     int *perm_src = nullptr, *perm_dst = nullptr, *perm_len = nullptr;   // caller -> internal
@@ -723,6 +726,33 @@ struct Engine : bamg_ctx {
         if (e & ERR_ZERODIAG) fail(BAMG_EZERODIAG, "b_ii <= 0 on the finest level");
     }
 
+    // ELL-4 copy of B_0 (and of its FP64 values in the mixed form) for the
+    // level-0 sweeps, the cycle's level-0 residual and the outer SpMV when
+    // every row has at most 4 entries (BAMG_SWEEP_ELL=0 turns it off).
+    void build_ell0() {
+        const char* e = getenv("BAMG_SWEEP_ELL");
+        if (e && e[0] == '0') return;
+        auto& lv = L[0];
+        const int rows = lv.rows;
+        if (get1(lv.B.rp + rows) > 4LL * rows) return;
+        int* eci = A.alloc<int>((size_t)rows * 4);
+        T* ev = A.alloc<T>((size_t)rows * 4);
+        zero(err, sizeof(int) * 4);
+        LAUNCH((k_csr_to_ell4<T>), nblk(rows), BAMG_BLK, s, rows, (const int*)lv.B.rp, (const int*)lv.B.ci,
+               (const T*)lv.B.v, eci, ev, err);
+        if (get1(err)) return;
+        lv.B.eci = eci;
+        lv.B.ev = ev;
+        if (MIXED) {
+            // same pattern: the column array is rewritten with the same values
+            b0ev = A.alloc<double>((size_t)rows * 4);
+            LAUNCH((k_csr_to_ell4<double>), nblk(rows), BAMG_BLK, s, rows, (const int*)b0rp, (const int*)b0ci,
+                   (const double*)b0v, eci, b0ev, err);
+        } else {
+            b0ev = (double*)ev;
+        }
+    }
+
     // -------------------------------------------------------------- setup steps
     // nu homogeneous sweeps on the continuing rows of level l (R columns).
     template <int VW, int BS>
@@ -730,6 +760,12 @@ struct Engine : bamg_ctx {
         const int G = R / VW;
         const long long tot = (long long)rows * G;
         const int grid = (int)std::max<long long>(1, (tot + BS - 1) / BS);
+        if (Bm.eci) {
+            hipLaunchKernelGGL((k_sweep_ve<T, T, VW, BS>), dim3(grid), dim3(BS), 0, s, rows, G, FastDiv((uint32_t)G),
+                               (const int*)Bm.eci, (const T*)Bm.ev, dinv, X, F, Y);
+            HIPCHK(hipGetLastError());
+            return;
+        }
         hipLaunchKernelGGL((k_sweep_v<T, T, VW, BS>), dim3(grid), dim3(BS), 0, s, rows, G, FastDiv((uint32_t)G),
                            (const int*)Bm.rp, (const int*)Bm.ci, (const T*)Bm.v, dinv, X, F, Y);
         HIPCHK(hipGetLastError());
@@ -1430,8 +1466,7 @@ struct Engine : bamg_ctx {
         const ChainGeo* g0 = L[0].dgeo;
         if (!rvec) rvec = A.alloc<double>(N);
         auto residual = [&]() {
-            LAUNCH(k_spmv<double>, nblk(N), BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)x0, -1.0,
-                   rvec, RowMask{g0, nch, nullptr});
+            outer_spmv((const double*)x0, -1.0, rvec, RowMask{g0, nch, nullptr});
             seg_reduce<RED_ABS>(rvec, nullptr, sc + 1);
             seg_reduce<RED_ABS>(x0, nullptr, sc + 2);
             std::vector<double> h = getn(sc, (size_t)SCS);
@@ -1452,8 +1487,7 @@ struct Engine : bamg_ctx {
         seg_reduce<RED_SUM>(x, nullptr, sc);
         LAUNCH(k_seg_scale, nblk(N), BAMG_BLK, s, N, g0, nch, (const int*)nullptr, (const double*)x,
                (const double*)nullptr, (const double*)sc, SCS, 0, x);
-        LAUNCH(k_spmv<double>, nblk(N), BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)x, -1.0, rvec,
-               RowMask{g0, nch, nullptr});
+        outer_spmv((const double*)x, -1.0, rvec, RowMask{g0, nch, nullptr});
         seg_reduce<RED_ABS>(rvec, nullptr, sc + 1);
         seg_reduce<RED_ABS>(x, nullptr, sc + 2);
         std::vector<double> h = getn(sc, (size_t)SCS);
@@ -1481,6 +1515,7 @@ struct Engine : bamg_ctx {
         allocate(nnzA);
         if (nch > 1) reorder_input(rp, ci, val, nnzA);
         build_b0(rp, ci, val, nnzA);
+        build_ell0();
         if (unstructured) check_symmetric();
         check_colours(0);
         const bool prof = o.profile != 0;
@@ -1537,6 +1572,9 @@ struct Engine : bamg_ctx {
         // D^-1, whose diagonal it takes from the rows)
         st.sweep_bytes = (long long)(n0 + 1) * 4 + (long long)nnz0 * (4 + vb) + (mcgs ? 0 : n0 * vb) +
                          2LL * n0 * r * vb;
+        st.sweep_ell = L[0].B.eci ? 1 : 0;
+        if (L[0].B.eci && !mcgs)         // the ELL-4 copy: 4 entries per row, no row pointers
+            st.sweep_bytes = 4LL * n0 * (4 + vb) + n0 * vb + 2LL * n0 * r * vb;
         if (L.size() > 1) {
             long long nc = L[1].rows;
             st.galerkin_bytes = nc * 9 * (4 + vb) + (long long)(n0 + 1) * 4 + (long long)nnz0 * (4 + vb) +
@@ -1545,7 +1583,28 @@ struct Engine : bamg_ctx {
         }
     }
 
+    // y = alpha * B_0 x in FP64 (the outer iteration), on the ELL-4 copy when
+    // there is one.
+    void outer_spmv(const double* x, double alpha, double* y, const RowMask& mk) {
+        const int N = (int)n;
+        if (b0ev)
+            LAUNCH(k_spmv_e<double>, nblk(N), BAMG_BLK, s, N, (const int*)L[0].B.eci, (const double*)b0ev, x, alpha, y,
+                   mk);
+        else
+            LAUNCH(k_spmv<double>, nblk(N), BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, x, alpha, y, mk);
+    }
+
     // -------------------------------------------------------------- cycle
+    // One smoothing sweep of the cycle on level lv: e_out = e + D^-1 (f - B e).
+    void cycle_sweep(Level<T>& lv, int rows, int nb, const T* cur, T* oth, const RowMask& mk) {
+        if (lv.B.eci)
+            LAUNCH((k_sweep_e<T, T>), nb, BAMG_BLK, s, rows, (const int*)lv.B.eci, (const T*)lv.B.ev,
+                   (const T*)lv.dinv, cur, (const T*)lv.f, oth, mk);
+        else
+            LAUNCH((k_sweep<T, T>), nb, BAMG_BLK, s, rows, 1, FastDiv(1u), lv.B.rp, lv.B.ci, (const T*)lv.B.v,
+                   (const T*)lv.dinv, cur, (const T*)lv.f, oth, mk);
+    }
+
     // e_l = C f_l on level l, result in lv.e (fixed buffers, so that the
     // cycle can be replayed from a graph).  Continuing chains smooth and
     // recurse; chains whose coarsest level is l take the minimal-norm solve.
@@ -1568,7 +1627,6 @@ struct Engine : bamg_ctx {
         if (lv.ncont == 0) return;
         auto& c = L[l + 1];
         const int rows = lv.cont_rows;
-        FastDiv d1(1u);
         T* cur = lv.zero_into_e2 ? lv.e2 : lv.e;
         T* oth = lv.zero_into_e2 ? lv.e : lv.e2;
         const int nb = nblk(rows);
@@ -1587,15 +1645,18 @@ struct Engine : bamg_ctx {
         } else if (o.nu_pre > 0) {
             LAUNCH((k_jacobi_zero<T, T>), nb, BAMG_BLK, s, rows, (const T*)lv.dinv, (const T*)lv.f, cur, mk);
             for (int k = 1; k < o.nu_pre; ++k) {
-                LAUNCH((k_sweep<T, T>), nb, BAMG_BLK, s, rows, 1, d1, lv.B.rp, lv.B.ci, (const T*)lv.B.v,
-                       (const T*)lv.dinv, (const T*)cur, (const T*)lv.f, oth, mk);
+                cycle_sweep(lv, rows, nb, cur, oth, mk);
                 std::swap(cur, oth);
             }
         } else {
             LAUNCH((k_fill_t<T>), nb, BAMG_BLK, s, rows, cur, mk);
         }
-        LAUNCH((k_residual<T, T>), nb, BAMG_BLK, s, rows, lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const T*)cur,
-               (const T*)lv.f, lv.r, mk);
+        if (lv.B.eci)
+            LAUNCH((k_residual_e<T, T>), nb, BAMG_BLK, s, rows, (const int*)lv.B.eci, (const T*)lv.B.ev,
+                   (const T*)cur, (const T*)lv.f, lv.r, mk);
+        else
+            LAUNCH((k_residual<T, T>), nb, BAMG_BLK, s, rows, lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const T*)cur,
+                   (const T*)lv.f, lv.r, mk);
         if (unstructured)
             LAUNCH(k_restrict_csr<T>, nblk(c.rows), BAMG_BLK, s, c.rows, (const int*)lv.qrp, (const int*)lv.qci,
                    (const T*)lv.qvv, (const T*)lv.r, c.f);
@@ -1610,8 +1671,7 @@ struct Engine : bamg_ctx {
             return;
         }
         for (int k = 0; k < o.nu_post; ++k) {
-            LAUNCH((k_sweep<T, T>), nb, BAMG_BLK, s, rows, 1, d1, lv.B.rp, lv.B.ci, (const T*)lv.B.v,
-                   (const T*)lv.dinv, (const T*)cur, (const T*)lv.f, oth, mk);
+            cycle_sweep(lv, rows, nb, cur, oth, mk);
             std::swap(cur, oth);
         }
         if (cur != lv.e) fail(BAMG_EDEVICE, "cycle buffer parity");
@@ -1733,8 +1793,7 @@ struct Engine : bamg_ctx {
         if (!hfail) hfail = A.alloc<int>(nch);
         std::vector<int> hact(nch, 1), hkd(nch, 0), done(nch, 0);
         auto residuals = [&](std::vector<double>& rel, std::vector<double>& nu) {
-            LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)xi, -1.0, rvec,
-                   RowMask{g0, nch, nullptr});
+            outer_spmv((const double*)xi, -1.0, rvec, RowMask{g0, nch, nullptr});
             seg_reduce<RED_ABS>(rvec, nullptr, sc + 1);
             seg_reduce<RED_ABS>(xi, nullptr, sc + 2);
             std::vector<double> h = getn(sc, (size_t)nch * SCS);
@@ -1765,8 +1824,7 @@ struct Engine : bamg_ctx {
             zero(Hg, sizeof(double) * nch * HSg);
             for (int j = 0; j < m && inf.cycles < max_cycles; ++j) {
                 // w = C (B v_j)
-                LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v,
-                       (const double*)(Vk + (size_t)j * N), 1.0, rvec, RowMask{g0, nch, act});
+                outer_spmv((const double*)(Vk + (size_t)j * N), 1.0, rvec, RowMask{g0, nch, act});
                 precondition(rvec, wk);
                 ++inf.cycles;
                 const int P0 = L[0].segp;
@@ -1869,8 +1927,7 @@ struct Engine : bamg_ctx {
         } else {
             for (;;) {
                 // r = -B x; per-chain relative 1-norm residual
-                LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)xi, -1.0, rvec,
-                       RowMask{g0, nch, nullptr});
+                outer_spmv((const double*)xi, -1.0, rvec, RowMask{g0, nch, nullptr});
                 seg_reduce<RED_ABS>(rvec, nullptr, sc + 1);
                 seg_reduce<RED_ABS>(xi, nullptr, sc + 2);
                 seg_reduce<RED_DOT>(rvec, rvec, sc + 3);
@@ -1912,8 +1969,7 @@ struct Engine : bamg_ctx {
                     }
                     precondition(vj, zj);
                     ++inf.cycles;
-                    LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)zj, 1.0, wk,
-                           RowMask{g0, nch, cmask});
+                    outer_spmv((const double*)zj, 1.0, wk, RowMask{g0, nch, cmask});
                     // Gram-Schmidt with the delayed second pass: dots of w, the
                     // per-chain step (finish v_j, correct column j-1, column j,
                     // Givens), and, for chains that go on, the update pass that
@@ -1962,8 +2018,7 @@ struct Engine : bamg_ctx {
         seg_reduce<RED_NEGSUM>(xi, nullptr, sc + 5);
         LAUNCH(k_clamp, nb, BAMG_BLK, s, N, xi);
         normalise();
-        LAUNCH(k_spmv<double>, nb, BAMG_BLK, s, N, b0rp, b0ci, (const double*)b0v, (const double*)xi, -1.0, rvec,
-               RowMask{g0, nch, nullptr});
+        outer_spmv((const double*)xi, -1.0, rvec, RowMask{g0, nch, nullptr});
         seg_reduce<RED_ABS>(rvec, nullptr, sc + 1);
         seg_reduce<RED_ABS>(xi, nullptr, sc + 2);
         if (reordered) {

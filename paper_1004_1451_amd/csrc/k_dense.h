@@ -558,10 +558,17 @@ __device__ void hqr_wave(int m, double* A, double* wr, double* wi, int* fail) {
     while (nn >= 0) {
         int its = 0, l;
         do {
-            for (l = nn; l >= 1; --l) {
-                double s = fabs(AA(l - 1, l - 1)) + fabs(AA(l, l));
-                if (s == 0.0) s = anorm;
-                if (fabs(AA(l, l - 1)) <= eps * s) break;
+            // l = the largest index in [1, nn] with a negligible subdiagonal
+            // entry (0 if none): every lane tests its own row at once
+            {
+                bool small = false;
+                if (lane >= 1 && lane <= nn) {
+                    double s = fabs(AA(lane - 1, lane - 1)) + fabs(AA(lane, lane));
+                    if (s == 0.0) s = anorm;
+                    small = fabs(AA(lane, lane - 1)) <= eps * s;
+                }
+                const unsigned long long mk = __ballot(small);
+                l = mk ? 63 - __clzll(mk) : 0;
             }
             lds_sync();
             if (l >= 1 && lane == 0) AA(l, l - 1) = 0.0;
@@ -629,7 +636,8 @@ __device__ void hqr_wave(int m, double* A, double* wr, double* wi, int* fail) {
                             r = (k != nn - 1) ? AA(k + 2, k - 1) : 0.0;
                             x = fabs(p) + fabs(q) + fabs(r);
                             if (x == 0.0) continue;
-                            p /= x; q /= x; r /= x;
+                            const double ix = 1.0 / x;
+                            p *= ix; q *= ix; r *= ix;
                         }
                         double s = sqrt(p * p + q * q + r * r);
                         if (p < 0) s = -s;
@@ -642,8 +650,9 @@ __device__ void hqr_wave(int m, double* A, double* wr, double* wi, int* fail) {
                             }
                         }
                         p += s;
-                        double hx = p / s, hy = q / s, hz = r / s;
-                        double qq = q / p, rr = r / p;
+                        const double is = 1.0 / s, ip = 1.0 / p;
+                        double hx = p * is, hy = q * is, hz = r * is;
+                        double qq = q * ip, rr = r * ip;
                         lds_sync();
                         {   // rows k..k+2, columns k..nn
                             int j = lane;
@@ -684,10 +693,12 @@ __device__ void hqr_wave(int m, double* A, double* wr, double* wi, int* fail) {
 // Packed upper triangle (complex): row k, column j >= k.
 __device__ __forceinline__ int upk(int m, int k, int j) { return k * m - (k * (k - 1)) / 2 + (j - k); }
 
-// z <- (H - theta I)^-1 z for the Hessenberg H (LDS, row-major m x m),
-// one wavefront; U (LDS, packed, 2 doubles per entry), z (LDS, complex).
-__device__ void hess_shift_solve_wave(int m, const double* __restrict__ H, double thr, double thi,
-                                      double* U, double* zr, double* zi, double hnorm) {
+// LU of (H - theta I) for the Hessenberg H (LDS, row-major m x m) with
+// pivoting between adjacent rows, one wavefront: U (LDS, packed, 2 doubles per
+// entry), the multiplier (fm[2k], fm[2k+1]) and swap flag swp[k] of step k.
+// Tiny pivots are replaced by 1e-14 ||H||.
+__device__ void hess_shift_factor_wave(int m, const double* __restrict__ H, double thr, double thi, double* U,
+                                       double* fm, int* swp, double hnorm) {
     const int lane = threadIdx.x;
     const double tiny = 1e-14 * hnorm;
     // current row k, lane j holds entry j
@@ -701,15 +712,10 @@ __device__ void hess_shift_solve_wave(int m, const double* __restrict__ H, doubl
         }
         double ckr = __shfl(cr, k, BAMG_WAVE), cki = __shfl(ci, k, BAMG_WAVE);
         double nkr = __shfl(nr, k, BAMG_WAVE), nki = __shfl(ni, k, BAMG_WAVE);
-        lds_sync();
-        bool swap = nkr * nkr + nki * nki > ckr * ckr + cki * cki;
+        const bool swap = nkr * nkr + nki * nki > ckr * ckr + cki * cki;
         if (swap) {
             double tr = cr, ti = ci; cr = nr; ci = ni; nr = tr; ni = ti;
             double a = ckr, b = cki; ckr = nkr; cki = nki; nkr = a; nki = b;
-            if (lane == 0) {
-                double t0 = zr[k], t1 = zi[k];
-                zr[k] = zr[k + 1]; zi[k] = zi[k + 1]; zr[k + 1] = t0; zi[k + 1] = t1;
-            }
         }
         if (ckr * ckr + cki * cki < tiny * tiny) {
             ckr = tiny; cki = 0.0;
@@ -717,7 +723,6 @@ __device__ void hess_shift_solve_wave(int m, const double* __restrict__ H, doubl
         }
         double d = ckr * ckr + cki * cki;
         double fr = (nkr * ckr + nki * cki) / d, fi = (nki * ckr - nkr * cki) / d;
-        lds_sync();
         if (lane >= k && lane < m) {
             int e = upk(m, k, lane);
             U[2 * e] = cr; U[2 * e + 1] = ci;
@@ -727,18 +732,33 @@ __device__ void hess_shift_solve_wave(int m, const double* __restrict__ H, doubl
         } else {
             cr = 0; ci = 0;
         }
-        if (lane == 0) {
-            double zkr = zr[k], zki = zi[k];
-            zr[k + 1] -= fr * zkr - fi * zki;
-            zi[k + 1] -= fr * zki + fi * zkr;
-        }
-        lds_sync();
+        if (lane == 0) { fm[2 * k] = fr; fm[2 * k + 1] = fi; swp[k] = swap ? 1 : 0; }
     }
     {
         int k = m - 1;
         double ckr = __shfl(cr, k, BAMG_WAVE), cki = __shfl(ci, k, BAMG_WAVE);
         if (ckr * ckr + cki * cki < tiny * tiny) { ckr = tiny; cki = 0.0; }
         if (lane == k) { int e = upk(m, k, k); U[2 * e] = ckr; U[2 * e + 1] = cki; }
+    }
+    lds_sync();
+}
+
+// z <- (H - theta I)^-1 z from the factors of hess_shift_factor_wave: the
+// recorded swaps and multipliers in step order, then back substitution.
+__device__ void hess_shift_apply_wave(int m, const double* U, const double* fm, const int* swp, double* zr,
+                                      double* zi) {
+    const int lane = threadIdx.x;
+    if (lane == 0) {
+        for (int k = 0; k < m - 1; ++k) {
+            if (swp[k]) {
+                double t0 = zr[k], t1 = zi[k];
+                zr[k] = zr[k + 1]; zi[k] = zi[k + 1]; zr[k + 1] = t0; zi[k + 1] = t1;
+            }
+            const double fr = fm[2 * k], fi = fm[2 * k + 1];
+            const double zkr = zr[k], zki = zi[k];
+            zr[k + 1] -= fr * zkr - fi * zki;
+            zi[k + 1] -= fr * zki + fi * zkr;
+        }
     }
     lds_sync();
     for (int i = m - 1; i >= 0; --i) {
@@ -778,8 +798,8 @@ __device__ void hessenberg_eig_body(int m, int want, const double* __restrict__ 
                                     double* __restrict__ sel_lam, double* __restrict__ sel_s) {
     __shared__ double A[HQR_MAXM * HQR_LD];
     __shared__ double Hs[HQR_MAXM * HQR_MAXM];
-    __shared__ double wr[HQR_MAXM], wi[HQR_MAXM], zr[HQR_MAXM], zi[HQR_MAXM];
-    __shared__ int used[HQR_MAXM];
+    __shared__ double wr[HQR_MAXM], wi[HQR_MAXM], zr[HQR_MAXM], zi[HQR_MAXM], fm[2 * HQR_MAXM];
+    __shared__ int used[HQR_MAXM], swp[HQR_MAXM];
     __shared__ int fail;
     const int lane = threadIdx.x;
     if (lane == 0) fail = 0;
@@ -823,8 +843,9 @@ __device__ void hessenberg_eig_body(int m, int want, const double* __restrict__ 
         if (lane == 0) { used[best] = 1; if (pj >= 0) used[pj] = 1; }
         if (lane < m) { zr[lane] = 1.0; zi[lane] = 0.0; }
         lds_sync();
+        hess_shift_factor_wave(m, Hs, thr, thi, A, fm, swp, hn);
         for (int itn = 0; itn < 3; ++itn) {
-            hess_shift_solve_wave(m, Hs, thr, thi, A, zr, zi, hn);
+            hess_shift_apply_wave(m, A, fm, swp, zr, zi);
             double s = lane < m ? zr[lane] * zr[lane] + zi[lane] * zi[lane] : 0.0;
             s = wave_sum(s);
             s = __shfl(s, 0, BAMG_WAVE);
@@ -861,7 +882,8 @@ __device__ void hessenberg_near_zero_body(int k, const double* __restrict__ Hh, 
                                           int* __restrict__ fail_out) {
     __shared__ double A[HQR_MAXM * HQR_LD];
     __shared__ double Hs[HQR_MAXM * HQR_MAXM];
-    __shared__ double wr[HQR_MAXM], wi[HQR_MAXM], zr[HQR_MAXM], zi[HQR_MAXM];
+    __shared__ double wr[HQR_MAXM], wi[HQR_MAXM], zr[HQR_MAXM], zi[HQR_MAXM], fm[2 * HQR_MAXM];
+    __shared__ int swp[HQR_MAXM];
     __shared__ int fail;
     const int lane = threadIdx.x;
     if (lane == 0) fail = 0;
@@ -887,8 +909,9 @@ __device__ void hessenberg_near_zero_body(int k, const double* __restrict__ Hh, 
     const double thr = wr[best], thi = wi[best];
     if (lane < k) { zr[lane] = 1.0; zi[lane] = 0.0; }
     lds_sync();
+    hess_shift_factor_wave(k, Hs, thr, thi, A, fm, swp, hn);
     for (int itn = 0; itn < 3; ++itn) {
-        hess_shift_solve_wave(k, Hs, thr, thi, A, zr, zi, hn);
+        hess_shift_apply_wave(k, A, fm, swp, zr, zi);
         double s = lane < k ? zr[lane] * zr[lane] + zi[lane] * zi[lane] : 0.0;
         s = wave_sum(s);
         s = __shfl(s, 0, BAMG_WAVE);

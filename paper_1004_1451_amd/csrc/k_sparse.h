@@ -226,6 +226,54 @@ k_residual(int n, const int* __restrict__ rp, const int* __restrict__ ci, const 
     r[i] = fi - acc;
 }
 
+// k_sweep (R = 1) and k_residual on the ELL-4 copy of B (see k_sweep_ve):
+// one row per thread, the row's columns and values in one 16-byte load each,
+// products added in CSR order with the same padding, so the results equal
+// the CSR kernels' bit for bit.
+template <typename T, typename M>
+__global__ void __launch_bounds__(BAMG_BLK)
+k_sweep_e(int n, const int* __restrict__ eci, const M* __restrict__ ev, const M* __restrict__ dinv,
+          const T* __restrict__ X, const T* __restrict__ F, T* __restrict__ Y, RowMask mk) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (!tile_active(mk, tile, BAMG_BLK, 1, n)) return;
+    const int i = tile * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    const int4 c4 = *(const int4*)(eci + (size_t)i * 4);
+    M w[4];
+    Ell4Val<M>::ld(ev + (size_t)i * 4, w);
+    const T xt = X[i];
+    const T d = (T)dinv[i];
+    const T f = F ? F[i] : (T)0;
+    const T x0 = X[c4.x], x1 = X[c4.y], x2 = X[c4.z], x3 = X[c4.w];
+    T acc = 0;
+    acc += (T)w[0] * x0;
+    acc += (T)w[1] * x1;
+    acc += (T)w[2] * x2;
+    acc += (T)w[3] * x3;
+    Y[i] = xt + d * (f - acc);
+}
+
+template <typename T, typename M>
+__global__ void __launch_bounds__(BAMG_BLK)
+k_residual_e(int n, const int* __restrict__ eci, const M* __restrict__ ev, const T* __restrict__ e,
+             const T* __restrict__ f, T* __restrict__ r, RowMask mk) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (!tile_active(mk, tile, BAMG_BLK, 1, n)) return;
+    const int i = tile * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    const int4 c4 = *(const int4*)(eci + (size_t)i * 4);
+    M w[4];
+    Ell4Val<M>::ld(ev + (size_t)i * 4, w);
+    const T fi = f ? f[i] : (T)0;
+    const T x0 = e[c4.x], x1 = e[c4.y], x2 = e[c4.z], x3 = e[c4.w];
+    T acc = 0;
+    acc += (T)w[0] * x0;
+    acc += (T)w[1] * x1;
+    acc += (T)w[2] * x2;
+    acc += (T)w[3] * x3;
+    r[i] = fi - acc;
+}
+
 // y = alpha * B x with FP64 vectors (values widened), used by the outer
 // iteration and the coarsest eigensolve.
 template <typename M>
@@ -237,6 +285,27 @@ k_spmv(int n, const int* __restrict__ rp, const int* __restrict__ ci, const M* _
     int i = tile * BAMG_BLK + threadIdx.x;
     if (i >= n) return;
     double acc = row_dot<double, M>(rp[i], rp[i + 1], ci, v, x, 1, 0, i);
+    y[i] = alpha * acc;
+}
+
+// k_spmv on the ELL-4 copy (see k_sweep_e): the same sums bit for bit.
+template <typename M>
+__global__ void __launch_bounds__(BAMG_BLK)
+k_spmv_e(int n, const int* __restrict__ eci, const M* __restrict__ ev, const double* __restrict__ x, double alpha,
+         double* __restrict__ y, RowMask mk) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (!tile_active(mk, tile, BAMG_BLK, 1, n)) return;
+    const int i = tile * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    const int4 c4 = *(const int4*)(eci + (size_t)i * 4);
+    M w[4];
+    Ell4Val<M>::ld(ev + (size_t)i * 4, w);
+    const double x0 = x[c4.x], x1 = x[c4.y], x2 = x[c4.z], x3 = x[c4.w];
+    double acc = 0;
+    acc += (double)w[0] * x0;
+    acc += (double)w[1] * x1;
+    acc += (double)w[2] * x2;
+    acc += (double)w[3] * x3;
     y[i] = alpha * acc;
 }
 

@@ -137,3 +137,72 @@ k_sweep_v(int n, int G, FastDiv divG, const int* __restrict__ rp, const int* __r
     VecIO<T, VW>::st(Y + base, y);
 }
 
+
+// The same sweep on a 4-wide ELL copy of B (row i's entries at 4i .. 4i+3 in
+// CSR order, padded with (i, 0)): the columns and values of a row arrive in
+// one 16-byte load each and no row pointer is read first.  Rows of B with at
+// most 4 entries only; the sums are those of k_sweep_v bit for bit.
+template <typename M>
+struct Ell4Val;
+template <> struct Ell4Val<float> {
+    static __device__ __forceinline__ void ld(const float* p, float* w) {
+        const float4 a = *(const float4*)p; w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+    }
+};
+template <> struct Ell4Val<double> {
+    static __device__ __forceinline__ void ld(const double* p, double* w) {
+        const double2 a = ((const double2*)p)[0], b = ((const double2*)p)[1];
+        w[0] = a.x; w[1] = a.y; w[2] = b.x; w[3] = b.y;
+    }
+};
+
+template <typename T, typename M, int VW, int BS>
+__global__ void __launch_bounds__(BS)
+k_sweep_ve(int n, int G, FastDiv divG, const int* __restrict__ eci, const M* __restrict__ ev,
+           const M* __restrict__ dinv, const T* __restrict__ X, const T* __restrict__ F, T* __restrict__ Y) {
+    const int t = xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
+    if (t >= n * G) return;
+    const int i = (int)divG.div((uint32_t)t), kg = t - i * G;
+    const int R = G * VW;
+    const size_t base = (size_t)i * R + (size_t)kg * VW;
+    const int4 c4 = *(const int4*)(eci + (size_t)i * 4);
+    M w[4];
+    Ell4Val<M>::ld(ev + (size_t)i * 4, w);
+    T xt[VW], f[VW], acc[VW];
+    VecIO<T, VW>::ld(X + base, xt);
+    if (F) VecIO<T, VW>::ld(F + base, f);
+    else
+#pragma unroll
+        for (int q = 0; q < VW; ++q) f[q] = (T)0;
+#pragma unroll
+    for (int q = 0; q < VW; ++q) acc[q] = (T)0;
+    const T d = (T)dinv[i];
+    const int c[4] = {c4.x, c4.y, c4.z, c4.w};
+    T x[4][VW];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) VecIO<T, VW>::ld(X + (size_t)c[u] * R + (size_t)kg * VW, x[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < VW; ++q) acc[q] += (T)w[u] * x[u][q];
+    T y[VW];
+#pragma unroll
+    for (int q = 0; q < VW; ++q) y[q] = xt[q] + d * (f[q] - acc[q]);
+    VecIO<T, VW>::st(Y + base, y);
+}
+
+// ELL-4 copy of a CSR matrix (see k_sweep_ve); err = 1 when a row has more
+// than 4 entries (the copy is then not used).
+template <typename M>
+__global__ void k_csr_to_ell4(int n, const int* __restrict__ rp, const int* __restrict__ ci, const M* __restrict__ v,
+                              int* __restrict__ eci, M* __restrict__ ev, int* __restrict__ err) {
+    const int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    const int p0 = rp[i], len = rp[i + 1] - p0;
+    if (len > 4) { *err = 1; return; }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        eci[(size_t)i * 4 + u] = u < len ? ci[p0 + u] : i;
+        ev[(size_t)i * 4 + u] = u < len ? v[p0 + u] : (M)0;
+    }
+}
