@@ -247,6 +247,8 @@ struct Csr {
     T* v = nullptr;
     int* eci = nullptr;              // ELL-4 copy (rows of at most 4 entries), or null
     T* ev = nullptr;
+    int* cci = nullptr;              // column-major ELL-9 copy (coarse grid levels), or null
+    T* cv = nullptr;
 };
 
 // Rows of one level: all present chains, continuing chains first.
@@ -933,6 +935,26 @@ struct Engine : bamg_ctx {
         }
         zero(err, sizeof(int) * 4);
         LAUNCH(k_dinv<T>, nblk(nc), BAMG_BLK, s, nc, c.B.rp, c.B.ci, c.B.v, o.omega, c.dinv, err);
+        build_ell9(l + 1);
+    }
+
+    // Column-major ELL-9 copy of B_l on a grid level below the finest (every
+    // coarse row lies in the 3 x 3 box), for the cycle's sweeps and residual
+    // (BAMG_SWEEP_ELL=0 turns it off).  Rebuilt with every Galerkin product.
+    void build_ell9(int l) {
+        const char* e = getenv("BAMG_SWEEP_ELL");
+        if (e && e[0] == '0') return;
+        auto& lv = L[l];
+        const int rows = lv.rows;
+        if (!lv.B.cci) {
+            lv.B.cci = A.alloc<int>((size_t)rows * 9);
+            lv.B.cv = A.alloc<T>((size_t)rows * 9);
+            invalidate_graph();
+        }
+        zero(err, sizeof(int) * 4);
+        LAUNCH((k_csr_to_ell9c<T>), nblk(rows), BAMG_BLK, s, rows, (const int*)lv.B.rp, (const int*)lv.B.ci,
+               (const T*)lv.B.v, lv.B.cci, lv.B.cv, err);
+        if (get1(err)) fail(BAMG_EDEVICE, "level %d has a row outside the 3 x 3 box", l);
     }
 
     void build_level(int l, int use_v, bool inject, bool profile) {
@@ -1597,7 +1619,10 @@ struct Engine : bamg_ctx {
     // -------------------------------------------------------------- cycle
     // One smoothing sweep of the cycle on level lv: e_out = e + D^-1 (f - B e).
     void cycle_sweep(Level<T>& lv, int rows, int nb, const T* cur, T* oth, const RowMask& mk) {
-        if (lv.B.eci)
+        if (lv.B.cci)
+            LAUNCH((k_sweep_c9<T, T>), nb, BAMG_BLK, s, rows, lv.rows, (const int*)lv.B.cci, (const T*)lv.B.cv,
+                   (const T*)lv.dinv, cur, (const T*)lv.f, oth, mk);
+        else if (lv.B.eci)
             LAUNCH((k_sweep_e<T, T>), nb, BAMG_BLK, s, rows, (const int*)lv.B.eci, (const T*)lv.B.ev,
                    (const T*)lv.dinv, cur, (const T*)lv.f, oth, mk);
         else
@@ -1643,15 +1668,32 @@ struct Engine : bamg_ctx {
             LAUNCH((k_fill_t<T>), nb, BAMG_BLK, s, rows, cur, mk);
             gs_sweeps(o.nu_pre);
         } else if (o.nu_pre > 0) {
-            LAUNCH((k_jacobi_zero<T, T>), nb, BAMG_BLK, s, rows, (const T*)lv.dinv, (const T*)lv.f, cur, mk);
-            for (int k = 1; k < o.nu_pre; ++k) {
+            int k = 1;
+            if (o.nu_pre >= 2 && (lv.B.cci || lv.B.eci)) {
+                // the zero-guess sweep and the next one in one pass, into the
+                // buffer the second would write
+                if (lv.B.cci)
+                    LAUNCH((k_sweep2z_c9<T, T>), nb, BAMG_BLK, s, rows, lv.rows, (const int*)lv.B.cci,
+                           (const T*)lv.B.cv, (const T*)lv.dinv, (const T*)lv.f, oth, mk);
+                else
+                    LAUNCH((k_sweep2z_e<T, T>), nb, BAMG_BLK, s, rows, (const int*)lv.B.eci, (const T*)lv.B.ev,
+                           (const T*)lv.dinv, (const T*)lv.f, oth, mk);
+                std::swap(cur, oth);
+                k = 2;
+            } else {
+                LAUNCH((k_jacobi_zero<T, T>), nb, BAMG_BLK, s, rows, (const T*)lv.dinv, (const T*)lv.f, cur, mk);
+            }
+            for (; k < o.nu_pre; ++k) {
                 cycle_sweep(lv, rows, nb, cur, oth, mk);
                 std::swap(cur, oth);
             }
         } else {
             LAUNCH((k_fill_t<T>), nb, BAMG_BLK, s, rows, cur, mk);
         }
-        if (lv.B.eci)
+        if (lv.B.cci)
+            LAUNCH((k_residual_c9<T, T>), nb, BAMG_BLK, s, rows, lv.rows, (const int*)lv.B.cci, (const T*)lv.B.cv,
+                   (const T*)cur, (const T*)lv.f, lv.r, mk);
+        else if (lv.B.eci)
             LAUNCH((k_residual_e<T, T>), nb, BAMG_BLK, s, rows, (const int*)lv.B.eci, (const T*)lv.B.ev,
                    (const T*)cur, (const T*)lv.f, lv.r, mk);
         else

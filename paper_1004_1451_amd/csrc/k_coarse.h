@@ -181,6 +181,32 @@ __device__ __forceinline__ void cz_gj(double (&S)[CZ_GJ_ROWS], int w, int c, int
     }
 }
 
+// In-place inverse of the diagonal block A[k0:k0+nb, k0:k0+nb] (ld) of the
+// dense Gauss-Jordan inverse: the block (padded to 64 x 64 with the identity)
+// in registers as cz_gj keeps it, two pivots per step.  Records min |pivot| /
+// scale in *minpiv (scale = max |B_L| entry; one workgroup runs this kernel).
+__global__ void __launch_bounds__(CZ_GJ_THREADS)
+k_gj_diag(int ld, int k0, int nb, double* __restrict__ A, const double* __restrict__ scale,
+          double* __restrict__ minpiv) {
+    __shared__ double prow[2][2][GJ_NB];
+    __shared__ double pcol[2][GJ_NB][2];
+    const int w = threadIdx.x / BAMG_WAVE, c = threadIdx.x % BAMG_WAVE;
+    double S[CZ_GJ_ROWS];
+#pragma unroll
+    for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+        const int r = CZ_GJ_ROWS * w + i;
+        S[i] = (r < nb && c < nb) ? A[(size_t)(k0 + r) * ld + k0 + c] : (r == c ? 1.0 : 0.0);
+    }
+    double mp = 1e300;
+    cz_gj(S, w, c, nb, *scale, mp, prow, pcol);
+#pragma unroll
+    for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+        const int r = CZ_GJ_ROWS * w + i;
+        if (r < nb && c < nb) A[(size_t)(k0 + r) * ld + k0 + c] = S[i];
+    }
+    if (threadIdx.x == 0) *minpiv = fmin(*minpiv, mp);
+}
+
 // One b x b product C = A B (mode 0, C may alias A) or C -= A B (mode 1):
 // A staged transposed and B as is in LDS (zero-padded to 64 x 64), each
 // thread a 4 x 4 tile of C at rows tr.., columns tc.., summed over t in

@@ -52,65 +52,6 @@ __global__ void k_absmax_partial(long long n, const double* __restrict__ a, doub
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-// In-place inverse of the diagonal block A[k0:k0+nb, k0:k0+nb] (ld) by
-// Gauss-Jordan without pivoting.  The block (padded to 64 x 64 with an
-// identity) lives in registers: thread t owns the 4 x 4 sub-block at rows
-// 4*(t/16), columns 4*(t%16).  Each step publishes the pivot row and column
-// in LDS (double-buffered, one barrier per step).  Records min |pivot| /
-// scale in *minpiv (scale = max |B_L| entry; one block runs this kernel).
-__global__ void __launch_bounds__(BAMG_BLK)
-k_gj_diag(int ld, int k0, int nb, double* __restrict__ A, const double* __restrict__ scale,
-          double* __restrict__ minpiv) {
-    // two copies of the block: step k reads copy k&1 and writes copy (k+1)&1
-    __shared__ double M[2][GJ_NB][GJ_NB + 1];
-    const int tid = threadIdx.x;
-    const int r0 = (tid / 16) * 4, c0 = (tid % 16) * 4;
-    double S[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            int r = r0 + a, c = c0 + b;
-            S[a][b] = (r < nb && c < nb) ? A[(size_t)(k0 + r) * ld + k0 + c] : (r == c ? 1.0 : 0.0);
-            M[0][r][c] = S[a][b];
-        }
-    const double sc = *scale;
-    double mp = 1e300;
-    __syncthreads();
-    for (int k = 0; k < GJ_NB; ++k) {
-        const int rd = k & 1, wr = rd ^ 1;
-        const double piv = M[rd][k][k];
-        const double ip = 1.0 / piv;
-        if (tid == 0 && k < nb) mp = fmin(mp, fabs(piv) / sc);
-        double f[4], pr[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) f[a] = M[rd][r0 + a][k];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) pr[b] = M[rd][k][c0 + b] * ip;
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const bool rk = (r0 + a) == k, ck = (c0 + b) == k;
-                double v = S[a][b] - f[a] * pr[b];
-                v = ck ? -f[a] * ip : v;
-                v = rk ? pr[b] : v;
-                v = (rk && ck) ? ip : v;
-                S[a][b] = v;
-                M[wr][r0 + a][c0 + b] = v;
-            }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            int r = r0 + a, c = c0 + b;
-            if (r < nb && c < nb) A[(size_t)(k0 + r) * ld + k0 + c] = S[a][b];
-        }
-    if (tid == 0) *minpiv = fmin(*minpiv, mp);
-}
-
 // Row panel: A[k0:k0+nb, j] = Dinv * A[k0:k0+nb, j] for j outside the block.
 // Block = 64 columns.
 __global__ void __launch_bounds__(BAMG_BLK)

@@ -288,6 +288,131 @@ k_spmv(int n, const int* __restrict__ rp, const int* __restrict__ ci, const M* _
     y[i] = alpha * acc;
 }
 
+// Column-major ELL-9 copy of a coarse operator (entry k of row i at k ld + i,
+// ld = the level's row count; the kernels below may run over a row prefix n;
+// CSR order, padded with (i, 0)): the one-row-per-thread cycle kernels load
+// the 9 columns and values of their rows with coalesced, independent loads.
+// err = 1 when a row has more than 9 entries.
+template <typename M>
+__global__ void k_csr_to_ell9c(int n, const int* __restrict__ rp, const int* __restrict__ ci, const M* __restrict__ v,
+                               int* __restrict__ cci, M* __restrict__ cv, int* __restrict__ err) {
+    const int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    const int p0 = rp[i], len = rp[i + 1] - p0;
+    if (len > 9) { *err = 1; return; }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        cci[(size_t)k * n + i] = k < len ? ci[p0 + k] : i;
+        cv[(size_t)k * n + i] = k < len ? v[p0 + k] : (M)0;
+    }
+}
+
+// sum_k v x over a row of the ELL-9 copy, k = 0..8 (the CSR order; the
+// padding adds exact zeros, as the CSR kernels' padding does).
+template <typename T, typename M>
+__device__ __forceinline__ T row_dot9c(int ld, int i, const int* __restrict__ cci, const M* __restrict__ cv,
+                                       const T* __restrict__ X) {
+    int c[9];
+    M w[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) { c[k] = cci[(size_t)k * ld + i]; w[k] = cv[(size_t)k * ld + i]; }
+    T x[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) x[k] = X[c[k]];
+    T acc = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc += (T)w[k] * x[k];
+    return acc;
+}
+
+template <typename T, typename M>
+__global__ void __launch_bounds__(BAMG_BLK)
+k_sweep_c9(int n, int ld, const int* __restrict__ cci, const M* __restrict__ cv, const M* __restrict__ dinv,
+           const T* __restrict__ X, const T* __restrict__ F, T* __restrict__ Y, RowMask mk) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (!tile_active(mk, tile, BAMG_BLK, 1, n)) return;
+    const int i = tile * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    const T xt = X[i];
+    const T d = (T)dinv[i];
+    const T f = F ? F[i] : (T)0;
+    const T acc = row_dot9c<T, M>(ld, i, cci, cv, X);
+    Y[i] = xt + d * (f - acc);
+}
+
+template <typename T, typename M>
+__global__ void __launch_bounds__(BAMG_BLK)
+k_residual_c9(int n, int ld, const int* __restrict__ cci, const M* __restrict__ cv, const T* __restrict__ e,
+              const T* __restrict__ f, T* __restrict__ r, RowMask mk) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (!tile_active(mk, tile, BAMG_BLK, 1, n)) return;
+    const int i = tile * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    const T fi = f ? f[i] : (T)0;
+    r[i] = fi - row_dot9c<T, M>(ld, i, cci, cv, e);
+}
+
+// The first two smoothing sweeps of the cycle from a zero guess in one pass:
+// e1 = D^-1 f (each e1_j formed as its own rounded product, as k_jacobi_zero
+// stores it), then y = e1 + D^-1 (f - B e1), on the ELL-4 (row-major) or the
+// ELL-9 (column-major, stride ld) copy.  Equal to k_jacobi_zero followed by
+// k_sweep_e / k_sweep_c9 bit for bit, without writing and re-reading e1.
+template <typename T, typename M>
+__global__ void __launch_bounds__(BAMG_BLK)
+k_sweep2z_e(int n, const int* __restrict__ eci, const M* __restrict__ ev, const M* __restrict__ dinv,
+            const T* __restrict__ F, T* __restrict__ Y, RowMask mk) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (!tile_active(mk, tile, BAMG_BLK, 1, n)) return;
+    const int i = tile * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    const int4 c4 = *(const int4*)(eci + (size_t)i * 4);
+    M w[4];
+    Ell4Val<M>::ld(ev + (size_t)i * 4, w);
+    const int c[4] = {c4.x, c4.y, c4.z, c4.w};
+    const T d = (T)dinv[i];
+    const T f = F[i];
+    T xt;
+    {
+#pragma clang fp contract(off)
+        xt = d * f;              // a rounded product, as e1_i is stored
+    }
+    T x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = (T)dinv[c[u]] * F[c[u]];
+    T acc = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += (T)w[u] * x[u];
+    Y[i] = xt + d * (f - acc);
+}
+
+template <typename T, typename M>
+__global__ void __launch_bounds__(BAMG_BLK)
+k_sweep2z_c9(int n, int ld, const int* __restrict__ cci, const M* __restrict__ cv, const M* __restrict__ dinv,
+             const T* __restrict__ F, T* __restrict__ Y, RowMask mk) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (!tile_active(mk, tile, BAMG_BLK, 1, n)) return;
+    const int i = tile * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    int c[9];
+    M w[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) { c[k] = cci[(size_t)k * ld + i]; w[k] = cv[(size_t)k * ld + i]; }
+    const T d = (T)dinv[i];
+    const T f = F[i];
+    T xt;
+    {
+#pragma clang fp contract(off)
+        xt = d * f;              // a rounded product, as e1_i is stored
+    }
+    T x[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) x[k] = (T)dinv[c[k]] * F[c[k]];
+    T acc = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc += (T)w[k] * x[k];
+    Y[i] = xt + d * (f - acc);
+}
+
 // k_spmv on the ELL-4 copy (see k_sweep_e): the same sums bit for bit.
 template <typename M>
 __global__ void __launch_bounds__(BAMG_BLK)
@@ -350,12 +475,18 @@ __global__ void k_prolong_add(int n, const int* __restrict__ pc, const M* __rest
     if (!tile_active(mk, tile, BAMG_BLK, 1, n)) return;
     int i = tile * BAMG_BLK + threadIdx.x;
     if (i >= n) return;
+    // the row's 4 slots in one 16-byte load each; empty slots add nothing
+    const int4 c4 = *(const int4*)(pc + (size_t)i * 4);
+    const int J[4] = {c4.x, c4.y, c4.z, c4.w};
+    M w[4];
+    Ell4Val<M>::ld(pv + (size_t)i * 4, w);
+    T x[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) x[s] = J[s] >= 0 ? ec[J[s]] : (T)0;
     T acc = 0;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        int J = pc[(size_t)i * 4 + s];
-        if (J >= 0) acc += (T)pv[(size_t)i * 4 + s] * ec[J];
-    }
+    for (int s = 0; s < 4; ++s)
+        if (J[s] >= 0) acc += (T)w[s] * x[s];
     e[i] += acc;
 }
 
