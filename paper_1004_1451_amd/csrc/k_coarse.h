@@ -317,6 +317,25 @@ k_cz_elim_arrow(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ F
 // touch none of the blocks workgroup 0 reads or writes, and their
 // multipliers follow in k_cz_elim_arrow.  One launch per block row instead
 // of three.
+// Columns t of row j of a block that couples two grid rows of the coarsest
+// level (3 x 3 box: |t - j| <= 1, wrapping on periodic grids), in ascending
+// order, -1 for none.  Such blocks (Lo, Up) are banded, so a product with
+// them takes 3 terms per entry.
+__device__ __forceinline__ void cz_band(int j, int b, int periodic, int (&t)[3]) {
+    int a0 = j - 1, a1 = j, a2 = j + 1;
+    if (periodic && b >= 3) {
+        if (a0 < 0) a0 += b;
+        if (a2 >= b) a2 -= b;
+        // ascending: the wrapped neighbour moves to the other end
+        if (j == 0) { t[0] = a1; t[1] = a2; t[2] = a0; return; }
+        if (j == b - 1) { t[0] = a2; t[1] = a0; t[2] = a1; return; }
+    } else {
+        if (a0 < 0) a0 = -1;
+        if (a2 >= b) a2 = -1;
+    }
+    t[0] = a0; t[1] = a1; t[2] = a2;
+}
+
 __global__ void __launch_bounds__(BAMG_BLK)
 k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, const double* __restrict__ scale,
              double* __restrict__ minpiv) {
@@ -324,6 +343,7 @@ k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, 
     __shared__ double lds[2 * GJ_NB * (GJ_NB + 2)];
     __shared__ __align__(16) double prow[2][2][GJ_NB];
     __shared__ __align__(16) double pcol[2][GJ_NB][2];
+    __shared__ double lob[GJ_NB][3];
     const CoarseDesc d = cd[blockIdx.y];
     const int K = d.nx - 1, q = blockIdx.x;
     const int kk = k < 0 ? K : k;
@@ -334,31 +354,35 @@ k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, 
             cz_elim_part(d, kk - 1, 1, q, Fp, (double(*)[GJ_NB + 2])lds, (double(*)[GJ_NB + 2])(lds + GJ_NB * (GJ_NB + 2)));
         return;
     }
-    double (*AsT)[GJ_NB + 2] = (double(*)[GJ_NB + 2])lds;
     double (*Bs)[GJ_NB + 2] = (double(*)[GJ_NB + 2])(lds + GJ_NB * (GJ_NB + 2));
     const int b = d.ny, tid = threadIdx.x;
     const int c = tid % BAMG_WAVE, w = tid / BAMG_WAVE;
-    const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
     double* D = cz_blk(Fp, d, 0, kk);
-    // the diagonal block and the next multiplier block are read at once, so
-    // their latency hides behind the first product
+    // the diagonal block and the band of the next multiplier block are read
+    // at once, so their latency hides behind the first product
     const bool mult = !arrow && kk < K;
     double* Lo1 = mult ? cz_blk(Fp, d, 2, kk + 1) : nullptr;
-    double Dv[CZ_GJ_ROWS], Lp[GJ_NB * GJ_NB / BAMG_BLK];
+    double Dv[CZ_GJ_ROWS];
 #pragma unroll
     for (int i = 0; i < CZ_GJ_ROWS; ++i) {
         const int r = CZ_GJ_ROWS * w + i;
         Dv[i] = (r < b && c < b) ? D[r * b + c] : 0.0;
     }
-#pragma unroll
-    for (int q4 = 0; q4 < GJ_NB * GJ_NB / BAMG_BLK; ++q4) {
-        const int e = tid + q4 * BAMG_BLK, r = e / GJ_NB, cc = e % GJ_NB;
-        Lp[q4] = (mult && r < b && cc < b) ? Lo1[r * b + cc] : 0.0;
+    // band of Lo_{k+1}: lob[r][s] = Lo[r][t_s], t_0 < t_1 < t_2 the columns of
+    // cz_band(r) (Lo couples grid rows k+1 and k within the 3 x 3 box)
+    if (mult && tid < 3 * GJ_NB) {
+        const int r = tid / 3, sl = tid % 3;
+        int t[3];
+        cz_band(r, b, d.periodic, t);
+        lob[r][sl] = (r < b && t[sl] >= 0) ? Lo1[r * b + t[sl]] : 0.0;
     }
     double S[CZ_GJ_ROWS];
-    if (kk >= 1) {
-        // Lo_k Up_{k-1} in 4 x 4 tiles, then through LDS into this
-        // thread's column strip
+    if (kk >= 1 && arrow) {
+        // periodic chains: the arrow elimination fills the block that couples
+        // the last two grid rows, so the product stays dense (4 x 4 tiles,
+        // then through LDS into this thread's column strip)
+        double (*AsT)[GJ_NB + 2] = (double(*)[GJ_NB + 2])lds;
+        const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
         cz_stage(b, cz_blk(Fp, d, 2, kk), AsT, cz_blk(Fp, d, 1, kk - 1), Bs);
         __syncthreads();
         double acc[4][4];
@@ -373,6 +397,27 @@ k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, 
         for (int i = 0; i < CZ_GJ_ROWS; ++i) {
             const int r = CZ_GJ_ROWS * w + i;
             S[i] = (r < b && c < b) ? Dv[i] - AsT[r][c] : (r == c ? 1.0 : 0.0);
+        }
+    } else if (kk >= 1) {
+        // S = D_k - M_k Up_{k-1}: Up_{k-1} is banded (never updated without
+        // the arrow), so column c of the product takes the columns
+        // cz_band(c) of M_k, in ascending order (the order of the dense sum,
+        // whose other terms add exact zeros)
+        const double* M = cz_blk(Fp, d, 2, kk);
+        const double* Up = cz_blk(Fp, d, 1, kk - 1);
+        int t[3];
+        cz_band(c, b, d.periodic, t);
+        double u[3];
+#pragma unroll
+        for (int sl = 0; sl < 3; ++sl) u[sl] = (c < b && t[sl] >= 0) ? Up[t[sl] * b + c] : 0.0;
+#pragma unroll
+        for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+            const int r = CZ_GJ_ROWS * w + i;
+            double acc = 0.0;
+#pragma unroll
+            for (int sl = 0; sl < 3; ++sl)
+                if (r < b && c < b && t[sl] >= 0) acc = fma(M[r * b + t[sl]], u[sl], acc);
+            S[i] = (r < b && c < b) ? Dv[i] - acc : (r == c ? 1.0 : 0.0);
         }
     } else {
 #pragma unroll
@@ -390,24 +435,24 @@ k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, 
     }
     if (tid == 0) minpiv[blockIdx.y] = fmin(minpiv[blockIdx.y], mp);
     if (mult) {
+        // M_{k+1} = Lo_{k+1} Dinv_k: row r takes the rows cz_band(r) of Dinv_k
+        // (its column c through LDS), in ascending order
         __syncthreads();
-#pragma unroll
-        for (int q4 = 0; q4 < GJ_NB * GJ_NB / BAMG_BLK; ++q4) {
-            const int e = tid + q4 * BAMG_BLK;
-            AsT[e % GJ_NB][e / GJ_NB] = Lp[q4];
-        }
 #pragma unroll
         for (int i = 0; i < CZ_GJ_ROWS; ++i) Bs[CZ_GJ_ROWS * w + i][c] = S[i];
         __syncthreads();
-        double acc[4][4];
-        cz_tile(b, AsT, Bs, tr, tc, acc);
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+            const int r = CZ_GJ_ROWS * w + i;
+            if (!(r < b && c < b)) continue;
+            int t[3];
+            cz_band(r, b, d.periodic, t);
+            double acc = 0.0;
 #pragma unroll
-            for (int q4 = 0; q4 < 4; ++q4) {
-                const int r = tr + a, cc = tc + q4;
-                if (r < b && cc < b) Lo1[r * b + cc] = acc[a][q4];
-            }
+            for (int sl = 0; sl < 3; ++sl)
+                if (t[sl] >= 0) acc = fma(lob[r][sl], Bs[t[sl]][c], acc);
+            Lo1[r * b + c] = acc;
+        }
     }
 }
 
