@@ -1018,18 +1018,28 @@ struct Engine : bamg_ctx {
             hipLaunchKernelGGL(k_cz_extract, dim3(nblk(bbmax), nxmax, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd,
                                (const double*)Wp, Fp);
             HIPCHK(hipGetLastError());
-            bool arrow = false;
-            for (auto& d : cdh) arrow |= d.periodic && d.nx >= 3;
-            const dim3 gl(arrow ? 4 : 1, nch);
-            for (int k = 0; k + 1 < nxmax; ++k) {
-                hipLaunchKernelGGL(k_cz_lu_step, gl, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, k, Fp,
-                                   (const double*)scale, minpiv);
-                if (arrow)
-                    hipLaunchKernelGGL(k_cz_elim_arrow, dim3(2, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, k, Fp);
-                HIPCHK(hipGetLastError());
+            bool arrow = false, plain = false;
+            for (auto& d : cdh) {
+                if (d.n < 2) continue;
+                if (d.periodic && d.nx >= 3) arrow = true; else plain = true;
             }
-            hipLaunchKernelGGL(k_cz_lu_step, gl, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, -1, Fp,
-                               (const double*)scale, minpiv);
+            // chains without the arrow: the whole factorisation in one launch
+            if (plain)
+                hipLaunchKernelGGL(k_cz_lu_all, dim3(nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, Fp,
+                                   (const double*)scale, minpiv);
+            if (arrow) {
+                const dim3 gl(4, nch);
+                for (int k = 0; k + 1 < nxmax; ++k) {
+                    hipLaunchKernelGGL(k_cz_lu_step, gl, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, k, Fp,
+                                       (const double*)scale, minpiv, 1);
+                    hipLaunchKernelGGL(k_cz_elim_arrow, dim3(2, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, k,
+                                       Fp);
+                    HIPCHK(hipGetLastError());
+                }
+                hipLaunchKernelGGL(k_cz_lu_step, gl, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, -1, Fp,
+                                   (const double*)scale, minpiv, 1);
+            }
+            HIPCHK(hipGetLastError());
             hipLaunchKernelGGL(k_cz_subst, dim3(ceil_div(maxnL, CZ_SUB_TC), nch), dim3(BAMG_BLK), 0, s,
                                (const CoarseDesc*)cd, Wp, (const double*)Fp);
             HIPCHK(hipGetLastError());

@@ -338,7 +338,7 @@ __device__ __forceinline__ void cz_band(int j, int b, int periodic, int (&t)[3])
 
 __global__ void __launch_bounds__(BAMG_BLK)
 k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, const double* __restrict__ scale,
-             double* __restrict__ minpiv) {
+             double* __restrict__ minpiv, int arrow_only) {
     static_assert(CZ_GJ_THREADS == BAMG_BLK, "one workgroup size for both parts");
     __shared__ double lds[2 * GJ_NB * (GJ_NB + 2)];
     __shared__ __align__(16) double prow[2][2][GJ_NB];
@@ -349,6 +349,7 @@ k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, 
     const int kk = k < 0 ? K : k;
     if (d.n < 2 || (k >= 0 && k >= K)) return;
     const bool arrow = d.periodic && d.nx >= 3;
+    if (arrow_only && !arrow) return;        // factored by k_cz_lu_all
     if (q > 0) {
         if (arrow && kk >= 1)
             cz_elim_part(d, kk - 1, 1, q, Fp, (double(*)[GJ_NB + 2])lds, (double(*)[GJ_NB + 2])(lds + GJ_NB * (GJ_NB + 2)));
@@ -454,6 +455,105 @@ k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, 
             Lo1[r * b + c] = acc;
         }
     }
+}
+
+// The whole block LU of a chain without the arrow (non-periodic grid) in one
+// launch, one workgroup per chain (blockIdx.x): block row after block row the
+// same steps as k_cz_lu_step with identical arithmetic, the multiplier M_k
+// kept in LDS from the step that forms it to the step that uses it, and the
+// next diagonal block and bands loaded before the current Gauss-Jordan, so
+// their latency and the launch gaps between rows disappear.  Chains with the
+// arrow return at once (k_cz_lu_step with arrow_only takes them).
+__global__ void __launch_bounds__(BAMG_BLK)
+k_cz_lu_all(const CoarseDesc* __restrict__ cd, double* __restrict__ Fp, const double* __restrict__ scale,
+            double* __restrict__ minpiv) {
+    __shared__ double Ms[GJ_NB][GJ_NB + 1];
+    __shared__ double Bs[GJ_NB][GJ_NB + 2];
+    __shared__ __align__(16) double prow[2][2][GJ_NB];
+    __shared__ __align__(16) double pcol[2][GJ_NB][2];
+    __shared__ double lob[GJ_NB][3];
+    const CoarseDesc d = cd[blockIdx.x];
+    if (d.n < 2 || (d.periodic && d.nx >= 3)) return;
+    const int K = d.nx - 1, b = d.ny, tid = threadIdx.x;
+    const int c = tid % BAMG_WAVE, w = tid / BAMG_WAVE;
+    const double sc = scale[blockIdx.x];
+    double mp = 1e300;
+    double Dn[CZ_GJ_ROWS];
+    {
+        const double* D0 = cz_blk(Fp, d, 0, 0);
+#pragma unroll
+        for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+            const int r = CZ_GJ_ROWS * w + i;
+            Dn[i] = (r < b && c < b) ? D0[r * b + c] : 0.0;
+        }
+    }
+    int tc[3];
+    cz_band(c, b, d.periodic, tc);
+    for (int kk = 0; kk <= K; ++kk) {
+        double* D = cz_blk(Fp, d, 0, kk);
+        const bool mult = kk < K;
+        double* Lo1 = mult ? cz_blk(Fp, d, 2, kk + 1) : nullptr;
+        if (mult && tid < 3 * GJ_NB) {
+            const int r = tid / 3, sl = tid % 3;
+            int t[3];
+            cz_band(r, b, d.periodic, t);
+            lob[r][sl] = (r < b && t[sl] >= 0) ? Lo1[r * b + t[sl]] : 0.0;
+        }
+        double u[3] = {0.0, 0.0, 0.0};
+        if (kk >= 1) {
+            const double* Up = cz_blk(Fp, d, 1, kk - 1);
+#pragma unroll
+            for (int sl = 0; sl < 3; ++sl) u[sl] = (c < b && tc[sl] >= 0) ? Up[tc[sl] * b + c] : 0.0;
+        }
+        double S[CZ_GJ_ROWS];
+#pragma unroll
+        for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+            const int r = CZ_GJ_ROWS * w + i;
+            double acc = 0.0;
+            if (kk >= 1) {
+#pragma unroll
+                for (int sl = 0; sl < 3; ++sl)
+                    if (r < b && c < b && tc[sl] >= 0) acc = fma(Ms[r][tc[sl]], u[sl], acc);
+            }
+            S[i] = (r < b && c < b) ? Dn[i] - acc : (r == c ? 1.0 : 0.0);
+        }
+        // the next diagonal block, while this one is inverted
+        if (mult) {
+            const double* D1 = cz_blk(Fp, d, 0, kk + 1);
+#pragma unroll
+            for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+                const int r = CZ_GJ_ROWS * w + i;
+                Dn[i] = (r < b && c < b) ? D1[r * b + c] : 0.0;
+            }
+        }
+        cz_gj(S, w, c, b, sc, mp, prow, pcol);
+#pragma unroll
+        for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+            const int r = CZ_GJ_ROWS * w + i;
+            if (r < b && c < b) D[r * b + c] = S[i];
+        }
+        if (mult) {
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < CZ_GJ_ROWS; ++i) Bs[CZ_GJ_ROWS * w + i][c] = S[i];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+                const int r = CZ_GJ_ROWS * w + i;
+                if (!(r < b && c < b)) continue;
+                int t[3];
+                cz_band(r, b, d.periodic, t);
+                double acc = 0.0;
+#pragma unroll
+                for (int sl = 0; sl < 3; ++sl)
+                    if (t[sl] >= 0) acc = fma(lob[r][sl], Bs[t[sl]][c], acc);
+                Lo1[r * b + c] = acc;
+                Ms[r][c] = acc;
+            }
+            __syncthreads();
+        }
+    }
+    if (tid == 0) minpiv[blockIdx.x] = fmin(minpiv[blockIdx.x], mp);
 }
 
 // All substitution steps of W = (L U)^-1 for one tile of CZ_SUB_TC columns
