@@ -607,7 +607,7 @@ __device__ int cz_subst_sequence(int K, bool arrow, int s0, int* seq) {
     }
     seq[m++] = K;                                              // Dinv_K
     for (int k = K - 1; k >= 0; --k) {
-        seq[m++] = (K + 1) + k;                                // Up_k
+        if (arrow) seq[m++] = (K + 1) + k;                     // Up_k (banded without the arrow: read directly)
         if (arrow && k < K - 1) seq[m++] = 3 * (K + 1) + k;   // Cl_k
         seq[m++] = k;                                          // Dinv_k
     }
@@ -704,7 +704,24 @@ k_cz_subst(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const dou
     __syncthreads();
     cz_put(T, Ks, tr, tc);
     cz_put(T, Xs, tr, tc);                           // X_{k+1} for k = K-1
-    // backward substitution
+    // backward substitution.  Without the arrow Up_k is banded (the 3 x 3
+    // box): its 3 band terms per row, in ascending column order, are read
+    // from memory (prefetched one step ahead) instead of staging the block.
+    double ub[4][3];
+    int tb[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) cz_band(tr + a, b, d.periodic, tb[a]);
+    auto load_band = [&](int k) {
+        const double* Up = F + (long long)((K + 1) + k) * bb;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int sl = 0; sl < 3; ++sl) {
+                const int r = tr + a, t = tb[a][sl];
+                ub[a][sl] = (r < b && t >= 0) ? Up[r * b + t] : 0.0;
+            }
+    };
+    if (!arrow && K >= 1) load_band(K - 1);
     for (int k = K - 1; k >= 0; --k) {
         double U[4];
 #pragma unroll
@@ -713,9 +730,20 @@ k_cz_subst(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const dou
             U[a] = (r < b && tc < w) ? W[(size_t)(k * b + r) * n + c0 + tc] : 0.0;
         }
         __syncthreads();
-        next_block();                                // Up_k
-        __syncthreads();
-        cz_mac(b, Ms, Xs, tr, tc, U, -1.0);
+        if (!arrow) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int sl = 0; sl < 3; ++sl) {
+                    const int t = tb[a][sl];
+                    if (tr + a < b && t >= 0) U[a] = fma(ub[a][sl], -1.0 * Xs[t][tc], U[a]);
+                }
+            if (k >= 1) load_band(k - 1);
+        } else {
+            next_block();                            // Up_k
+            __syncthreads();
+            cz_mac(b, Ms, Xs, tr, tc, U, -1.0);
+        }
         if (arrow && k < K - 1) {
             __syncthreads();
             next_block();                            // Cl_k
@@ -774,11 +802,35 @@ k_cz_gemv_f32(const CoarseDesc* __restrict__ cd, const float* __restrict__ Wp, c
     const CoarseDesc d = cd[blockIdx.y];
     const float* W = Wp + d.woff;
     const int lane = threadIdx.x % BAMG_WAVE;
+    // Lane L sums the column groups 4j .. 4j+3, j = L, L + 64, ..., in column
+    // order, then tail column 4 (n / 4) + L; with 16-byte aligned rows and
+    // vector each group is one 16-byte load, otherwise four scalar loads in
+    // the same order (so the sum does not depend on the alignment).
+    const int n4 = d.n / 4;
+    const bool v4 = (d.n & 3) == 0 && (d.row0 & 3) == 0 && (d.woff & 3) == 0;
     for (int row = blockIdx.x * (BAMG_BLK / BAMG_WAVE) + threadIdx.x / BAMG_WAVE; row < d.n;
          row += gridDim.x * (BAMG_BLK / BAMG_WAVE)) {
         const float* a = W + (size_t)row * d.n;
+        const float* xr = x + d.row0;
         float s = 0;
-        for (int j = lane; j < d.n; j += BAMG_WAVE) s += a[j] * x[d.row0 + j];
+        if (v4) {
+            const float4* a4 = (const float4*)a;
+            const float4* x4 = (const float4*)xr;
+            // 16 groups per lane cover a 4096-column row: all loads in flight
+#pragma unroll 16
+            for (int j = lane; j < n4; j += BAMG_WAVE) {
+                const float4 av = a4[j], xv = x4[j];
+                s += av.x * xv.x;
+                s += av.y * xv.y;
+                s += av.z * xv.z;
+                s += av.w * xv.w;
+            }
+        } else {
+            for (int j = lane; j < n4; j += BAMG_WAVE)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) s += a[4 * j + q] * xr[4 * j + q];
+            if (4 * n4 + lane < d.n) s += a[4 * n4 + lane] * xr[4 * n4 + lane];
+        }
         s = wave_sum(s);
         if (lane == 0) out[d.row0 + row] = s;
     }
@@ -792,11 +844,30 @@ k_cz_gemv_rows(const CoarseDesc* __restrict__ cd, const double* __restrict__ Wp,
     const CoarseDesc d = cd[blockIdx.y];
     const double* W = Wp + d.woff;
     const int lane = threadIdx.x % BAMG_WAVE;
+    // column pairs per lane, as in k_cz_gemv_f32 with groups of 2
+    const int n2 = d.n / 2;
+    const bool v2 = (d.n & 1) == 0 && (d.row0 & 1) == 0 && (d.woff & 1) == 0;
     for (int row = blockIdx.x * (BAMG_BLK / BAMG_WAVE) + threadIdx.x / BAMG_WAVE; row < d.n;
          row += gridDim.x * (BAMG_BLK / BAMG_WAVE)) {
         const double* a = W + (size_t)row * d.n;
+        const double* xr = x + d.row0;
         double s = 0;
-        for (int j = lane; j < d.n; j += BAMG_WAVE) s += a[j] * x[d.row0 + j];
+        if (v2) {
+            const double2* a2 = (const double2*)a;
+            const double2* x2 = (const double2*)xr;
+#pragma unroll 16
+            for (int j = lane; j < n2; j += BAMG_WAVE) {
+                const double2 av = a2[j], xv = x2[j];
+                s += av.x * xv.x;
+                s += av.y * xv.y;
+            }
+        } else {
+            for (int j = lane; j < n2; j += BAMG_WAVE) {
+                s += a[2 * j] * xr[2 * j];
+                s += a[2 * j + 1] * xr[2 * j + 1];
+            }
+            if (2 * n2 + lane < d.n) s += a[2 * n2 + lane] * xr[2 * n2 + lane];
+        }
         s = wave_sum(s);
         if (lane == 0) out[d.row0 + row] = s;
     }
