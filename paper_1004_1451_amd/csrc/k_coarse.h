@@ -774,6 +774,34 @@ __global__ void k_cz_zero_border(const CoarseDesc* __restrict__ cd, double* __re
     }
 }
 
+// sum_{j < m} a[j] x[j] by one wavefront (result in every lane): lane L takes
+// the column pairs 2q, 2q + 1 (q = L, L + 64, ...) in order, then the tail
+// column 2 (m / 2) + L.  One 16-byte load per pair when a and x are 16-byte
+// aligned, two 8-byte loads otherwise: the same sum either way.
+__device__ __forceinline__ double wave_row_dot(const double* __restrict__ a, const double* __restrict__ x, int m,
+                                               int lane) {
+    const int m2 = m / 2;
+    double s = 0;
+    if (((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(x)) & 15) == 0) {
+        const double2* a2 = (const double2*)a;
+        const double2* x2 = (const double2*)x;
+#pragma unroll 16
+        for (int q = lane; q < m2; q += BAMG_WAVE) {
+            const double2 av = a2[q], xv = x2[q];
+            s += av.x * xv.x;
+            s += av.y * xv.y;
+        }
+    } else {
+        for (int q = lane; q < m2; q += BAMG_WAVE) {
+            s += a[2 * q] * x[2 * q];
+            s += a[2 * q + 1] * x[2 * q + 1];
+        }
+    }
+    if (2 * m2 + lane < m) s += a[2 * m2 + lane] * x[2 * m2 + lane];
+    s = wave_sum(s);
+    return __shfl(s, 0, BAMG_WAVE);
+}
+
 // out[voff + i] = sum_j W[i, j] x[voff + j] (i < rows(d), j < cols(d)):
 // one wavefront per row.  which = 0: rows = cols = n; 1: rows = cols = n-1.
 __global__ void __launch_bounds__(BAMG_BLK)
@@ -785,10 +813,7 @@ k_cz_gemv(const CoarseDesc* __restrict__ cd, int which, const double* __restrict
     const int lane = threadIdx.x % BAMG_WAVE;
     for (int row = blockIdx.x * (BAMG_BLK / BAMG_WAVE) + threadIdx.x / BAMG_WAVE; row < m;
          row += gridDim.x * (BAMG_BLK / BAMG_WAVE)) {
-        const double* a = W + (size_t)row * d.n;
-        double s = 0;
-        for (int j = lane; j < m; j += BAMG_WAVE) s += a[j] * x[d.voff + j];
-        s = wave_sum(s);
+        const double s = wave_row_dot(W + (size_t)row * d.n, x + d.voff, m, lane);
         if (lane == 0) out[d.voff + row] = s;
     }
 }
@@ -844,31 +869,9 @@ k_cz_gemv_rows(const CoarseDesc* __restrict__ cd, const double* __restrict__ Wp,
     const CoarseDesc d = cd[blockIdx.y];
     const double* W = Wp + d.woff;
     const int lane = threadIdx.x % BAMG_WAVE;
-    // column pairs per lane, as in k_cz_gemv_f32 with groups of 2
-    const int n2 = d.n / 2;
-    const bool v2 = (d.n & 1) == 0 && (d.row0 & 1) == 0 && (d.woff & 1) == 0;
     for (int row = blockIdx.x * (BAMG_BLK / BAMG_WAVE) + threadIdx.x / BAMG_WAVE; row < d.n;
          row += gridDim.x * (BAMG_BLK / BAMG_WAVE)) {
-        const double* a = W + (size_t)row * d.n;
-        const double* xr = x + d.row0;
-        double s = 0;
-        if (v2) {
-            const double2* a2 = (const double2*)a;
-            const double2* x2 = (const double2*)xr;
-#pragma unroll 16
-            for (int j = lane; j < n2; j += BAMG_WAVE) {
-                const double2 av = a2[j], xv = x2[j];
-                s += av.x * xv.x;
-                s += av.y * xv.y;
-            }
-        } else {
-            for (int j = lane; j < n2; j += BAMG_WAVE) {
-                s += a[2 * j] * xr[2 * j];
-                s += a[2 * j + 1] * xr[2 * j + 1];
-            }
-            if (2 * n2 + lane < d.n) s += a[2 * n2 + lane] * xr[2 * n2 + lane];
-        }
-        s = wave_sum(s);
+        const double s = wave_row_dot(W + (size_t)row * d.n, x + d.row0, d.n, lane);
         if (lane == 0) out[d.row0 + row] = s;
     }
 }
@@ -1026,10 +1029,7 @@ k_cz_arn_gemv(const CoarseDesc* __restrict__ cd, int j, const double* __restrict
     const int lane = threadIdx.x % BAMG_WAVE;
     for (int row = blockIdx.x * (BAMG_BLK / BAMG_WAVE) + threadIdx.x / BAMG_WAVE; row < d.n;
          row += gridDim.x * (BAMG_BLK / BAMG_WAVE)) {
-        const double* a = W + (size_t)row * d.n;
-        double s = 0;
-        for (int q = lane; q < d.n; q += BAMG_WAVE) s += a[q] * w[d.voff + q];
-        s = wave_sum(s);
+        const double s = wave_row_dot(W + (size_t)row * d.n, w + d.voff, d.n, lane);
         if (lane == 0) u[row] = s;
     }
 }
