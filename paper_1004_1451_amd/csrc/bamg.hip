@@ -205,6 +205,39 @@ bool forced_sweep_shape(int R, SweepShape& out) {
     return true;
 }
 
+// HIP events are reused process-wide (per device): creating one costs host
+// time that would otherwise show as idle GPU time between launches.
+struct EventPool {
+    std::mutex mu;
+    std::map<int, std::vector<hipEvent_t>> free;
+    hipEvent_t get() {
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            auto& v = free[dev];
+            if (!v.empty()) {
+                hipEvent_t e = v.back();
+                v.pop_back();
+                return e;
+            }
+        }
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        return e;
+    }
+    void put(hipEvent_t e) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) { (void)hipEventDestroy(e); return; }
+        std::lock_guard<std::mutex> lk(mu);
+        free[dev].push_back(e);
+    }
+};
+EventPool& event_pool() {
+    static EventPool* p = new EventPool();   // never destroyed: outlives every handle
+    return *p;
+}
+
 struct Arena {
     hipStream_t s = nullptr;
     size_t bytes = 0, budget = 0;
@@ -361,6 +394,8 @@ struct Engine : bamg_ctx {
     double* sc = nullptr;            // nch x SCS per-chain scalars
     double* wts = nullptr;           // nch x WS TV weights
     int* err = nullptr;
+    int* derr = nullptr;             // error flags checked once, at the end of the setup
+    int* gath = nullptr;             // scalars gathered for one read-back
     int *itmp = nullptr, *bsum = nullptr, *total = nullptr;
     T* sweep_tmp = nullptr;
     // FGMRES
@@ -391,7 +426,7 @@ struct Engine : bamg_ctx {
         if (graph) (void)hipGraphDestroy(graph);
         if (cap_s) (void)hipStreamDestroy(cap_s);
         for (auto* v : {&ev_sweep, &ev_gal, &ev_ls, &ev_gj})
-            for (auto& p : *v) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
+            for (auto& p : *v) { event_pool().put(p.first); event_pool().put(p.second); }
         A.release();
     }
 
@@ -434,8 +469,8 @@ struct Engine : bamg_ctx {
 
     std::pair<hipEvent_t, hipEvent_t> ev_begin() {
         std::pair<hipEvent_t, hipEvent_t> p;
-        HIPCHK(hipEventCreate(&p.first));
-        HIPCHK(hipEventCreate(&p.second));
+        p.first = event_pool().get();
+        p.second = event_pool().get();
         HIPCHK(hipEventRecord(p.first, s));
         return p;
     }
@@ -606,6 +641,9 @@ struct Engine : bamg_ctx {
         sc = A.alloc<double>((size_t)nch * SCS);
         wts = A.alloc<double>((size_t)nch * WS);
         err = A.alloc<int>(4);
+        derr = A.alloc<int>(1);
+        zero(derr, sizeof(int));
+        gath = A.alloc<int>(72);
         itmp = A.alloc<int>(n + 1);
         bsum = A.alloc<int>(nblk(n) + 1);
         total = A.alloc<int>(4);
@@ -736,7 +774,7 @@ struct Engine : bamg_ctx {
         if (e && e[0] == '0') return;
         auto& lv = L[0];
         const int rows = lv.rows;
-        if (get1(lv.B.rp + rows) > 4LL * rows) return;
+        if (nnz0 > 4LL * rows) return;
         int* eci = A.alloc<int>((size_t)rows * 4);
         T* ev = A.alloc<T>((size_t)rows * 4);
         zero(err, sizeof(int) * 4);
@@ -806,7 +844,9 @@ struct Engine : bamg_ctx {
         if ((long long)rows * R < (1LL << 20)) return sh;
         int dev = 0;
         HIPCHK(hipGetDevice(&dev));
-        const int nnz = get1(lv.B.rp + rows);
+        // (the key only separates shapes: level 0 by its nnz, the others by
+        // their rows, without a read-back)
+        const int nnz = l == 0 ? nnz0 : -1;
         auto key = std::make_tuple(dev, rows, R, nnz, (int)sizeof(T));
         auto& tu = sweep_tuner();
         {
@@ -820,8 +860,8 @@ struct Engine : bamg_ctx {
             for (int bs : {128, 256, 512})
                 if (R % vw == 0 && (vw == 1 || vw == 2 || vw == 4 || bs <= 256)) cand.push_back({vw, bs});
         hipEvent_t a, b;
-        HIPCHK(hipEventCreate(&a));
-        HIPCHK(hipEventCreate(&b));
+        a = event_pool().get();
+        b = event_pool().get();
         sweep_shape(cand[0], rows, R, lv.B, lv.dinv, X, nullptr, scratch);     // warm-up
         float bestms = 1e30f;
         for (auto& c : cand) {
@@ -833,8 +873,8 @@ struct Engine : bamg_ctx {
             HIPCHK(hipEventElapsedTime(&ms, a, b));
             if (ms < bestms) { bestms = ms; sh = c; }
         }
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
+        event_pool().put(a);
+        event_pool().put(b);
         std::lock_guard<std::mutex> lk(tu.mu);
         tu.best[key] = sh;
         tu.tune_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -951,10 +991,10 @@ struct Engine : bamg_ctx {
             lv.B.cv = A.alloc<T>((size_t)rows * 9);
             invalidate_graph();
         }
-        zero(err, sizeof(int) * 4);
+        // a row above 9 entries cannot come out of the box-masked product; the
+        // flag is read with the other deferred checks at the end of the setup
         LAUNCH((k_csr_to_ell9c<T>), nblk(rows), BAMG_BLK, s, rows, (const int*)lv.B.rp, (const int*)lv.B.ci,
-               (const T*)lv.B.v, lv.B.cci, lv.B.cv, err);
-        if (get1(err)) fail(BAMG_EDEVICE, "level %d has a row outside the 3 x 3 box", l);
+               (const T*)lv.B.v, lv.B.cci, lv.B.cv, derr);
     }
 
     void build_level(int l, int use_v, bool inject, bool profile) {
@@ -1572,8 +1612,14 @@ struct Engine : bamg_ctx {
         st.t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         st.n_levels = (int)L.size();
         st.n_v = nvmax;
+        // every level's nnz(B) and the deferred error flags in one read-back
+        const int nl = (int)L.size();
+        for (int l = 0; l < nl; ++l) LAUNCH(k_copy_int, 1, BAMG_WAVE, s, (const int*)(L[l].B.rp + L[l].rows), gath + l);
+        LAUNCH(k_copy_int, 1, BAMG_WAVE, s, (const int*)derr, gath + nl);
+        std::vector<int> g = getn(gath, (size_t)nl + 1);
+        if (g[nl]) fail(BAMG_EDEVICE, "a coarse grid operator has a row outside the 3 x 3 box");
         long long tot = 0;
-        for (auto& lv : L) tot += get1(lv.B.rp + lv.rows);
+        for (int l = 0; l < nl; ++l) tot += g[l];
         st.op_complexity = nnz0 > 0 ? (double)tot / nnz0 : 0.0;
         auto acc = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, double& ms, int& cnt) {
             ms = 0; cnt = 0;
@@ -1581,7 +1627,7 @@ struct Engine : bamg_ctx {
                 float t = 0;
                 HIPCHK(hipEventElapsedTime(&t, p.first, p.second));
                 ms += t; ++cnt;
-                (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second);
+                event_pool().put(p.first); event_pool().put(p.second);
             }
             v.clear();
         };
@@ -1733,8 +1779,11 @@ struct Engine : bamg_ctx {
     // How a cycle is issued: options.cycle_mode 1 = eager launches, 2 = one
     // captured graph replayed per cycle, 0 = decide on the first cycle: it
     // runs eagerly, timed on the host (launch cost) and on the stream (GPU
-    // time); the graph is used when launching takes over half the GPU time,
-    // i.e. when the cycle is launch-bound (small chains, coarse levels).
+    // time); the graph is used when launching takes longer than the GPU
+    // time, i.e. when the cycle is launch-bound (small chains, coarse
+    // levels).  Otherwise eager launches stay ahead of the GPU and the graph's
+    // capture and instantiation (a few hundred microseconds per handle) would
+    // not pay back.
     void run_cycle() {
         if (!cycle_decided) {
             cycle_decided = true;
@@ -1742,8 +1791,8 @@ struct Engine : bamg_ctx {
                 use_graph = o.cycle_mode == 2;
             } else {
                 hipEvent_t a, b;
-                HIPCHK(hipEventCreate(&a));
-                HIPCHK(hipEventCreate(&b));
+                a = event_pool().get();
+                b = event_pool().get();
                 HIPCHK(hipEventRecord(a, s));
                 auto t0 = std::chrono::steady_clock::now();
                 vcycle(0);
@@ -1753,11 +1802,11 @@ struct Engine : bamg_ctx {
                 HIPCHK(hipEventSynchronize(b));
                 float ms = 0;
                 HIPCHK(hipEventElapsedTime(&ms, a, b));
-                (void)hipEventDestroy(a);
-                (void)hipEventDestroy(b);
+                event_pool().put(a);
+                event_pool().put(b);
                 st.cycle_host_us = host_us;
                 st.cycle_gpu_us = 1e3 * ms;
-                use_graph = host_us > 0.5 * 1e3 * ms;
+                use_graph = host_us > 1e3 * ms;
                 st.cycle_graph = use_graph ? 1 : 0;
                 return;                          // this cycle has run
             }

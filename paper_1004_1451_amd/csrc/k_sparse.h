@@ -413,6 +413,11 @@ k_sweep2z_c9(int n, int ld, const int* __restrict__ cci, const M* __restrict__ c
     Y[i] = xt + d * (f - acc);
 }
 
+// dst[0] = src[0] (gathers scalars of several arrays for one read-back).
+__global__ void k_copy_int(const int* __restrict__ src, int* __restrict__ dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = src[0];
+}
+
 // k_spmv on the ELL-4 copy (see k_sweep_e): the same sums bit for bit.
 template <typename M>
 __global__ void __launch_bounds__(BAMG_BLK)
