@@ -76,6 +76,40 @@ constexpr int SEG_ROWS = 1024;
 // The TV-weight and Rayleigh partials do a sparse product per (row, column)
 // on top of the sum: shorter chunks keep many workgroups in flight.
 constexpr int CN_ROWS = 256;
+// Pad (doubles) after each Krylov basis vector.
+constexpr int GS_PAD_DEFAULT = 640;   // 5 KiB
+
+// Row stride of the Krylov bases: n rounded up to 256 bytes, plus a pad so
+// that the vectors do not all start at the same offset modulo a large power
+// of two (the passes read 20 to 50 of them at the same row index, and equal
+// offsets fall on the same HBM channel).  BAMG_GS_PAD overrides the pad (in
+// doubles, rounded up to a multiple of 32).
+static int basis_stride(int n) {
+    static const int pad = [] {
+        const char* e = std::getenv("BAMG_GS_PAD");
+        const int p = e ? std::max(0, std::atoi(e)) : GS_PAD_DEFAULT;
+        return (p + 31) / 32 * 32;
+    }();
+    return (n + 31) / 32 * 32 + pad;
+}
+
+// Calls f(std::integral_constant<int, K>) with K the multiple of 8 (8 .. 64)
+// that covers nb finished basis vectors: the register width of the
+// Gram-Schmidt passes.
+template <typename F>
+static void gs_dispatch(int nb, F&& f) {
+    switch ((std::max(nb, 1) + 7) / 8) {
+        case 1: f(std::integral_constant<int, 8>{}); break;
+        case 2: f(std::integral_constant<int, 16>{}); break;
+        case 3: f(std::integral_constant<int, 24>{}); break;
+        case 4: f(std::integral_constant<int, 32>{}); break;
+        case 5: f(std::integral_constant<int, 40>{}); break;
+        case 6: f(std::integral_constant<int, 48>{}); break;
+        case 7: f(std::integral_constant<int, 56>{}); break;
+        case 8: f(std::integral_constant<int, 64>{}); break;
+        default: throw std::logic_error("Gram-Schmidt basis wider than 64");
+    }
+}
 constexpr int WS = 64;            // stride of the per-chain TV weights
 constexpr int KV = 16;            // stride of the per-chain eigen tables
 constexpr int SCS = 16;           // stride of the per-chain scalars
@@ -401,6 +435,7 @@ struct Engine : bamg_ctx {
     // FGMRES
     int m_alloc = 0;
     double *hbuf2 = nullptr, *gsaux = nullptr, *gscoef = nullptr;
+    int vld = 0;   // row stride of the Krylov bases Vk, Zk (n rounded up, plus a pad)
     double *Vk = nullptr, *Zk = nullptr, *wk = nullptr, *Hg = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr,
            *ysol = nullptr, *hbuf = nullptr, *rvec = nullptr, *est = nullptr, *xperm = nullptr;
     int *act = nullptr, *kd = nullptr;
@@ -1925,17 +1960,15 @@ struct Engine : bamg_ctx {
             zero(Hg, sizeof(double) * nch * HSg);
             for (int j = 0; j < m && inf.cycles < max_cycles; ++j) {
                 // w = C (B v_j)
-                outer_spmv((const double*)(Vk + (size_t)j * N), 1.0, rvec, RowMask{g0, nch, act});
+                outer_spmv((const double*)(Vk + (size_t)j * vld), 1.0, rvec, RowMask{g0, nch, act});
                 precondition(rvec, wk);
                 ++inf.cycles;
                 const int P0 = L[0].segp;
                 const dim3 gsg(P0, nch);
-                auto pick = [&](auto k8, auto k16, auto k32, auto k64) {
-                    return j <= 8 ? k8 : j <= 16 ? k16 : j <= 32 ? k32 : k64;
-                };
-                hipLaunchKernelGGL(pick(k_gs_dots<8>, k_gs_dots<16>, k_gs_dots<32>, k_gs_dots<64>), gsg,
-                                   dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, N, j, (const int*)act, (const double*)Vk,
-                                   (const double*)wk, part, GS);
+                gs_dispatch(j, [&](auto kc) {
+                    hipLaunchKernelGGL(k_gs_dots<decltype(kc)::value>, gsg, dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, vld, j,
+                                       (const int*)act, (const double*)Vk, (const double*)wk, part, GS);
+                });
                 hipLaunchKernelGGL(k_gs_final, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0,
                                    (const int*)act, (const double*)part, GS, hbuf, GS);
                 HIPCHK(hipGetLastError());
@@ -1946,8 +1979,8 @@ struct Engine : bamg_ctx {
                        hfail);
                 for (int c = 0; c < nch; ++c) hkd[c] = j + 1;
                 HIPCHK(hipMemcpyAsync(kd, hkd.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
-                LAUNCH(k_seg_ritz, nb, BAMG_BLK, s, N, g0, nch, (const int*)act, (const int*)kd, (const double*)Vk,
-                       (const double*)ysol, GS, xi);
+                LAUNCH(k_seg_ritz, nb, BAMG_BLK, s, N, vld, g0, nch, (const int*)act, (const int*)kd,
+                       (const double*)Vk, (const double*)ysol, GS, xi);
                 // sum one, on the chains that moved only (the others keep their bits)
                 seg_reduce<RED_SUM>(xi, nullptr, sc);
                 LAUNCH(k_seg_scale, nb, BAMG_BLK, s, N, g0, nch, (const int*)act, (const double*)xi,
@@ -1964,9 +1997,10 @@ struct Engine : bamg_ctx {
                 }
                 if (!cont || j + 1 >= m || inf.cycles >= max_cycles) break;
                 HIPCHK(hipMemcpyAsync(act, hact.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
-                hipLaunchKernelGGL(pick(k_gs_update<8>, k_gs_update<16>, k_gs_update<32>, k_gs_update<64>), gsg,
-                                   dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, N, j, (const int*)act, Vk, (const double*)wk,
-                                   (const double*)gscoef, part, GS);
+                gs_dispatch(j, [&](auto kc) {
+                    hipLaunchKernelGGL(k_gs_update<decltype(kc)::value>, gsg, dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, vld,
+                                       j, (const int*)act, Vk, (const double*)wk, (const double*)gscoef, part, GS);
+                });
                 hipLaunchKernelGGL(k_gs_final, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0,
                                    (const int*)act, (const double*)part, GS, hbuf2, GS);
                 HIPCHK(hipGetLastError());
@@ -1985,8 +2019,9 @@ struct Engine : bamg_ctx {
         const int ld = m + 1;
         const int HSg = (m + 1) * m, GS = m + 2;
         if (m_alloc != m) {
-            Vk = A.alloc<double>((size_t)(m + 1) * N);
-            Zk = A.alloc<double>((size_t)m * N);
+            vld = basis_stride(N);
+            Vk = A.alloc<double>((size_t)(m + 1) * vld);
+            Zk = A.alloc<double>((size_t)m * vld);
             wk = A.alloc<double>(N);
             rvec = A.alloc<double>(N);
             Hg = A.alloc<double>((size_t)nch * HSg);
@@ -2059,8 +2094,8 @@ struct Engine : bamg_ctx {
                 LAUNCH(k_seg_scale, nb, BAMG_BLK, s, N, g0, nch, (const int*)nullptr, (const double*)rvec,
                        (const double*)nullptr, (const double*)(sc + 3), SCS, 1, Vk);
                 for (int j = 0; j < m && inf.cycles < max_cycles; ++j) {
-                    double* vj = Vk + (size_t)j * N;
-                    double* zj = Zk + (size_t)j * N;
+                    double* vj = Vk + (size_t)j * vld;
+                    double* zj = Zk + (size_t)j * vld;
                     // once most chains have stopped, the masked cycle is little
                     // work in many launches: replay it from a graph instead
                     if (nch > 1 && o.cycle_mode == 0 && cycle_decided && !use_graph) {
@@ -2077,12 +2112,10 @@ struct Engine : bamg_ctx {
                     // finishes q_j and makes v_{j+1} with its dots
                     const int P0 = L[0].segp;
                     const dim3 gsg(P0, nch);
-                    auto pick = [&](auto k8, auto k16, auto k32, auto k64) {
-                        return j <= 8 ? k8 : j <= 16 ? k16 : j <= 32 ? k32 : k64;
-                    };
-                    hipLaunchKernelGGL(pick(k_gs_dots<8>, k_gs_dots<16>, k_gs_dots<32>, k_gs_dots<64>), gsg, dim3(BAMG_BLK),
-                                       0, s, g0, SEG_ROWS, N, j, (const int*)act, (const double*)Vk, (const double*)wk,
-                                       part, GS);
+                    gs_dispatch(j, [&](auto kc) {
+                        hipLaunchKernelGGL(k_gs_dots<decltype(kc)::value>, gsg, dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, vld,
+                                           j, (const int*)act, (const double*)Vk, (const double*)wk, part, GS);
+                    });
                     hipLaunchKernelGGL(k_gs_final, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0,
                                        (const int*)act, (const double*)part, GS, hbuf, GS);
                     HIPCHK(hipGetLastError());
@@ -2099,9 +2132,10 @@ struct Engine : bamg_ctx {
                     }
                     if (!any || j + 1 >= m || inf.cycles >= max_cycles) break;
                     HIPCHK(hipMemcpyAsync(act, hact.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
-                    hipLaunchKernelGGL(pick(k_gs_update<8>, k_gs_update<16>, k_gs_update<32>, k_gs_update<64>), gsg,
-                                       dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, N, j, (const int*)act, Vk, (const double*)wk,
-                                       (const double*)gscoef, part, GS);
+                    gs_dispatch(j, [&](auto kc) {
+                        hipLaunchKernelGGL(k_gs_update<decltype(kc)::value>, gsg, dim3(BAMG_BLK), 0, s, g0, SEG_ROWS,
+                                           vld, j, (const int*)act, Vk, (const double*)wk, (const double*)gscoef, part, GS);
+                    });
                     hipLaunchKernelGGL(k_gs_final, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0,
                                        (const int*)act, (const double*)part, GS, hbuf2, GS);
                     HIPCHK(hipGetLastError());
@@ -2109,8 +2143,8 @@ struct Engine : bamg_ctx {
                 HIPCHK(hipMemcpyAsync(kd, hkd.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
                 LAUNCH(k_seg_gmres_y, ceil_div(nch, 64), 64, s, nch, ld, (const int*)kd, (const double*)Hg, HSg,
                        (const double*)g, GS, ysol);
-                LAUNCH(k_seg_xupdate, nb, BAMG_BLK, s, N, g0, nch, (const int*)kd, (const double*)Zk, (const double*)ysol,
-                       GS, xi);
+                LAUNCH(k_seg_xupdate, nb, BAMG_BLK, s, N, vld, g0, nch, (const int*)kd, (const double*)Zk,
+                       (const double*)ysol, GS, xi);
                 normalise();
                 ++inf.restarts;
             }

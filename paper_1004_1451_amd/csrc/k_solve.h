@@ -277,49 +277,66 @@ __global__ void k_seg_reduce_final(const ChainGeo* __restrict__ geo, int seg_row
 #define GS_CS (2 * GS_MAXB + 4)
 
 template <int K>
-__device__ __forceinline__ void gs_store_partials(double (&acc)[K], double ey, double ex, int nb,
+__device__ __forceinline__ void gs_store_partials(double (&acc_k)[K], double ey, double ex, int nb,
                                                   double* __restrict__ part, int NDM, double* red) {
-    constexpr int SH = K >= 64 ? 0 : K >= 32 ? 1 : K >= 16 ? 2 : 3;
-    static_assert((BAMG_WAVE >> SH) == K, "K must be 8, 16, 32 or 64");
+    // the lane reduction runs on the next power of two (8 .. 64) of K, so a
+    // dot's summation order depends only on that power, not on K itself
+    constexpr int KR = K <= 8 ? 8 : K <= 16 ? 16 : K <= 32 ? 32 : 64;
+    constexpr int SH = KR >= 64 ? 0 : KR >= 32 ? 1 : KR >= 16 ? 2 : 3;
+    static_assert((BAMG_WAVE >> SH) == KR && K <= KR, "K must be at most 64");
+    double acc[KR];
+#pragma unroll
+    for (int b = 0; b < KR; ++b) acc[b] = b < K ? acc_k[b] : 0.0;
     const int lane = threadIdx.x % BAMG_WAVE, wv = threadIdx.x / BAMG_WAVE;
-    wave_sum_many<K>(acc);
+    wave_sum_many<KR>(acc);
     ey = wave_sum(ey);
     ex = wave_sum(ex);
-    if ((lane & ((1 << SH) - 1)) == 0) red[wv * (K + 2) + (lane >> SH)] = acc[0];
-    if (lane == 0) { red[wv * (K + 2) + K] = ey; red[wv * (K + 2) + K + 1] = ex; }
+    if ((lane & ((1 << SH) - 1)) == 0) red[wv * (KR + 2) + (lane >> SH)] = acc[0];
+    if (lane == 0) { red[wv * (KR + 2) + KR] = ey; red[wv * (KR + 2) + KR + 1] = ex; }
     __syncthreads();
     const int t = threadIdx.x;
     if (t < nb + 2) {
-        const int src = t < nb ? t : K + (t - nb);
+        const int src = t < nb ? t : KR + (t - nb);
         double v = 0;
 #pragma unroll
-        for (int q = 0; q < BAMG_BLK / BAMG_WAVE; ++q) v += red[q * (K + 2) + src];
+        for (int q = 0; q < BAMG_BLK / BAMG_WAVE; ++q) v += red[q * (KR + 2) + src];
         part[((size_t)blockIdx.y * NDM + t) * gridDim.x + blockIdx.x] = v;
     }
 }
 
+// Reduction scratch of the passes (per wave: the KR + 2 sums of a row block).
+template <int K>
+struct GsRed { static constexpr int KR = K <= 8 ? 8 : K <= 16 ? 16 : K <= 32 ? 32 : 64; };
+
 // Dots pass: <q_b, w> (b < nb), <v_nb, w>, <w, w> on a chunk of one chain.
-// K >= nb accumulators per thread; grid (chunks, chains).
+// K >= nb accumulators per thread (K a multiple of 8); grid (chunks, chains).
+// V_b starts at V + b ldv.  Every thread issues all K loads of a row
+// unconditionally (b >= nb re-reads v_nb, a cache hit) so that they are in
+// flight together; the sums b >= nb are never stored.
 template <int K>
 __global__ void __launch_bounds__(BAMG_BLK)
-k_gs_dots(const ChainGeo* __restrict__ geo, int seg_rows, int N, int nb, const int* __restrict__ act,
+k_gs_dots(const ChainGeo* __restrict__ geo, int seg_rows, int ldv, int nb, const int* __restrict__ act,
           const double* __restrict__ V, const double* __restrict__ w, double* __restrict__ part, int NDM) {
-    __shared__ double red[(BAMG_BLK / BAMG_WAVE) * (K + 2)];
+    __shared__ double red[(BAMG_BLK / BAMG_WAVE) * (GsRed<K>::KR + 2)];
     const ChainGeo g = geo[blockIdx.y];
     if (!act[blockIdx.y]) return;
     const int i0 = g.off + blockIdx.x * seg_rows, i1 = min(g.off + g.n, i0 + seg_rows);
     if (i0 >= i1) return;
-    const double* y = V + (size_t)nb * N;
+    const double* y = V + (size_t)nb * ldv;
     double acc[K];
 #pragma unroll
     for (int b = 0; b < K; ++b) acc[b] = 0.0;
     double ey = 0.0, ex = 0.0;
     for (int i = i0 + threadIdx.x; i < i1; i += BAMG_BLK) {
         const double x = w[i];
+        double q[K];
 #pragma unroll
-        for (int b = 0; b < K; ++b)
-            if (b < nb) acc[b] += V[(size_t)b * N + i] * x;
-        ey += y[i] * x;
+        for (int b = 0; b < K; ++b) q[b] = (b < nb ? V + (size_t)b * ldv : y)[i];
+        const double yi = y[i];
+        __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the products
+#pragma unroll
+        for (int b = 0; b < K; ++b) acc[b] += q[b] * x;
+        ey += yi * x;
         ex += x * x;
     }
     gs_store_partials<K>(acc, ey, ex, nb, part, NDM, red);
@@ -330,21 +347,29 @@ k_gs_dots(const ChainGeo* __restrict__ geo, int seg_rows, int N, int nb, const i
 // [+1] h, [+2] 1/nu):  q_nb = (v_nb - sum a_b q_b) / alpha over V_nb (not
 // rewritten for nb = 0, where v_0 is exact), v_{nb+1} = (w - sum d_b q_b -
 // h q_nb) / nu into V_{nb+1}, then the dots of v_{nb+1}.  The q_b of a row
-// are loaded once into registers (K >= nb) for the updates and the dots.
+// are loaded once into registers (K >= nb, all K loads issued together; b >=
+// nb re-reads v_nb with a zero coefficient, which leaves the sums unchanged)
+// for the updates and the dots; the coefficients sit in LDS.
 template <int K>
 __global__ void __launch_bounds__(BAMG_BLK)
-k_gs_update(const ChainGeo* __restrict__ geo, int seg_rows, int N, int nb, const int* __restrict__ act,
+k_gs_update(const ChainGeo* __restrict__ geo, int seg_rows, int ldv, int nb, const int* __restrict__ act,
             double* __restrict__ V, const double* __restrict__ w, const double* __restrict__ coef,
             double* __restrict__ part, int NDM) {
-    __shared__ double red[(BAMG_BLK / BAMG_WAVE) * (K + 2)];
+    __shared__ double red[(BAMG_BLK / BAMG_WAVE) * (GsRed<K>::KR + 2)];
+    __shared__ double sa[K], sd[K];
     const ChainGeo g = geo[blockIdx.y];
     if (!act[blockIdx.y]) return;
     const int i0 = g.off + blockIdx.x * seg_rows, i1 = min(g.off + g.n, i0 + seg_rows);
     if (i0 >= i1) return;
     const double* cf = coef + (size_t)blockIdx.y * GS_CS;
+    for (int t = threadIdx.x; t < K; t += BAMG_BLK) {
+        sa[t] = t < nb ? cf[t] : 0.0;
+        sd[t] = t < nb ? cf[GS_MAXB + t] : 0.0;
+    }
     const double ia = cf[2 * GS_MAXB], hh = cf[2 * GS_MAXB + 1], inu = cf[2 * GS_MAXB + 2];
-    double* y = V + (size_t)nb * N;
-    double* xn = V + (size_t)(nb + 1) * N;
+    __syncthreads();
+    double* y = V + (size_t)nb * ldv;
+    double* xn = V + (size_t)(nb + 1) * ldv;
     double acc[K];
 #pragma unroll
     for (int b = 0; b < K; ++b) acc[b] = 0.0;
@@ -352,22 +377,20 @@ k_gs_update(const ChainGeo* __restrict__ geo, int seg_rows, int N, int nb, const
     for (int i = i0 + threadIdx.x; i < i1; i += BAMG_BLK) {
         double q[K];
 #pragma unroll
-        for (int b = 0; b < K; ++b) q[b] = b < nb ? V[(size_t)b * N + i] : 0.0;
+        for (int b = 0; b < K; ++b) q[b] = (b < nb ? V + (size_t)b * ldv : y)[i];
         double t = y[i];
+        double x = w[i];
+        __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the products
 #pragma unroll
-        for (int b = 0; b < K; ++b)
-            if (b < nb) t -= cf[b] * q[b];
+        for (int b = 0; b < K; ++b) t -= sa[b] * q[b];
         t *= ia;
         if (nb > 0) y[i] = t;
-        double x = w[i];
 #pragma unroll
-        for (int b = 0; b < K; ++b)
-            if (b < nb) x -= cf[GS_MAXB + b] * q[b];
+        for (int b = 0; b < K; ++b) x -= sd[b] * q[b];
         x = (x - hh * t) * inu;
         xn[i] = x;
 #pragma unroll
-        for (int b = 0; b < K; ++b)
-            if (b < nb) acc[b] += q[b] * x;
+        for (int b = 0; b < K; ++b) acc[b] += q[b] * x;
         ey += t * x;
         ex += x * x;
     }
@@ -545,7 +568,8 @@ __global__ void k_arn_step(int nch, int j, int ld, const int* __restrict__ act, 
 }
 
 // x_i = sum_{b < kd[c]} eta_b V_b[i] on the rows of chains with act[c].
-__global__ void k_seg_ritz(int N, const ChainGeo* __restrict__ geo, int nch, const int* __restrict__ act,
+// (V_b starts at V + b ldv.)
+__global__ void k_seg_ritz(int N, int ldv, const ChainGeo* __restrict__ geo, int nch, const int* __restrict__ act,
                            const int* __restrict__ kd, const double* __restrict__ V, const double* __restrict__ etaall,
                            int ES, double* __restrict__ x) {
     const int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
@@ -555,7 +579,7 @@ __global__ void k_seg_ritz(int N, const ChainGeo* __restrict__ geo, int nch, con
     const int k = kd[c];
     const double* eta = etaall + (size_t)c * ES;
     double s = 0.0;
-    for (int b = 0; b < k; ++b) s += eta[b] * V[(size_t)b * N + i];
+    for (int b = 0; b < k; ++b) s += eta[b] * V[(size_t)b * ldv + i];
     x[i] = s;
 }
 
@@ -583,8 +607,8 @@ __global__ void k_seg_gmres_y(int nch, int ld, const int* __restrict__ kd, const
     }
 }
 
-// x += sum_{j < kd[c]} y_cj Z_j.
-__global__ void k_seg_xupdate(int N, const ChainGeo* __restrict__ geo, int nch, const int* __restrict__ kd,
+// x += sum_{j < kd[c]} y_cj Z_j (Z_j at Z + j ldv).
+__global__ void k_seg_xupdate(int N, int ldv, const ChainGeo* __restrict__ geo, int nch, const int* __restrict__ kd,
                               const double* __restrict__ Z, const double* __restrict__ yall, int GS,
                               double* __restrict__ x) {
     int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
@@ -593,7 +617,7 @@ __global__ void k_seg_xupdate(int N, const ChainGeo* __restrict__ geo, int nch, 
     const int k = kd[c];
     const double* y = yall + (size_t)c * GS;
     double s = x[i];
-    for (int j = 0; j < k; ++j) s += y[j] * Z[(size_t)j * N + i];
+    for (int j = 0; j < k; ++j) s += y[j] * Z[(size_t)j * ldv + i];
     x[i] = s;
 }
 
