@@ -134,6 +134,13 @@ __device__ __forceinline__ double cz_recip(double p) {
     return fma(r, e, r);
 }
 
+// Lane l's value of v (l uniform across the wave), without LDS.
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)u, l), hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Gauss-Jordan on the 64 x 64 block held in S by the CZ_GJ_THREADS threads
 // (w = wave, c = lane), two pivots per step: with the pivot block
 // P = A[J, J], J = {s, s+1}, and its closed-form inverse Q,
@@ -141,11 +148,17 @@ __device__ __forceinline__ double cz_recip(double p) {
 //   A[r, c] <- A[r, c] - A[r, J] Q A[J, c]  (r, c outside J),
 // the same Schur complements as two scalar steps.  Each entry takes two
 // fused multiply-adds; the pivot columns use m = e_j + Q[:, j] so the same
-// update leaves -A[r, J] Q there.  mp takes the smallest |scalar pivot| / sc
-// of the first nb (a and det / a per block).
+// update leaves -A[r, J] Q there.  A wave's rows of the pivot columns sit in
+// its own lanes s and s+1 (read with v_readlane); only the two pivot rows go
+// through LDS, from the wave that holds them.  mp (thread 0) takes the
+// smallest |scalar pivot| / sc of the first nb (a and det / a per block):
+// thread t keeps step t's pair and the quotients and their minimum are
+// formed once at the end, off the chain of dependent steps.
 __device__ __forceinline__ void cz_gj(double (&S)[CZ_GJ_ROWS], int w, int c, int nb, double sc, double& mp,
-                                      double (*prow)[2][GJ_NB], double (*pcol)[GJ_NB][2]) {
+                                      double (*prow)[2][GJ_NB]) {
     static_assert(CZ_GJ_ROWS % 2 == 0, "pivot pairs stay inside one wave");
+    static_assert(GJ_NB == BAMG_WAVE, "lane = column of the block");
+    double my_a = 1.0, my_det = 1.0;
     for (int blk = 0; blk < GJ_NB / CZ_GJ_ROWS; ++blk) {
 #pragma unroll
         for (int ss = 0; ss < CZ_GJ_ROWS / 2; ++ss) {
@@ -153,31 +166,37 @@ __device__ __forceinline__ void cz_gj(double (&S)[CZ_GJ_ROWS], int w, int c, int
             const int j = c - s0;
             const bool cj = j == 0 || j == 1;
             if (w == blk) { prow[buf][0][c] = S[2 * ss]; prow[buf][1][c] = S[2 * ss + 1]; }
-            if (cj)
+            double fx[CZ_GJ_ROWS], fy[CZ_GJ_ROWS];
 #pragma unroll
-                for (int i = 0; i < CZ_GJ_ROWS; ++i) pcol[buf][CZ_GJ_ROWS * w + i][j] = S[i];
+            for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+                fx[i] = readlane_f64(S[i], s0);
+                fy[i] = readlane_f64(S[i], s0 + 1);
+            }
             __syncthreads();
             const double a = prow[buf][0][s0], b = prow[buf][0][s0 + 1];
             const double cc = prow[buf][1][s0], d = prow[buf][1][s0 + 1];
+            const double r0 = prow[buf][0][c], r1 = prow[buf][1][c];
             const double det = fma(a, d, -b * cc);
             const double id = cz_recip(det);
             const double q00 = d * id, q01 = -b * id, q10 = -cc * id, q11 = a * id;
-            if (threadIdx.x == 0) {
-                if (s0 < nb) mp = fmin(mp, fabs(a) / sc);
-                if (s0 + 1 < nb) mp = fmin(mp, fabs(det / a) / sc);
-            }
-            const double r0 = prow[buf][0][c], r1 = prow[buf][1][c];
+            if (threadIdx.x == s0 / 2) { my_a = a; my_det = det; }
             const double g0 = fma(q00, r0, q01 * r1), g1 = fma(q10, r0, q11 * r1);
             const double p0 = j == 0 ? q00 : q01, p1 = j == 0 ? q10 : q11;     // column j of Q
             const double m0 = cj ? (j == 0 ? 1.0 : 0.0) + p0 : g0;
             const double m1 = cj ? (j == 1 ? 1.0 : 0.0) + p1 : g1;
 #pragma unroll
-            for (int i = 0; i < CZ_GJ_ROWS; ++i) {
-                const double2 f = *(const double2*)&pcol[buf][CZ_GJ_ROWS * w + i][0];
-                S[i] = fma(-f.x, m0, fma(-f.y, m1, S[i]));
-            }
+            for (int i = 0; i < CZ_GJ_ROWS; ++i) S[i] = fma(-fx[i], m0, fma(-fy[i], m1, S[i]));
             if (w == blk) { S[2 * ss] = cj ? p0 : g0; S[2 * ss + 1] = cj ? p1 : g1; }
         }
+    }
+    if (threadIdx.x < BAMG_WAVE) {
+        const int s0 = 2 * threadIdx.x;
+        double v = 1e300;
+        if (s0 < GJ_NB && s0 < nb) v = fmin(v, fabs(my_a) / sc);
+        if (s0 < GJ_NB && s0 + 1 < nb) v = fmin(v, fabs(my_det / my_a) / sc);
+#pragma unroll
+        for (int o = BAMG_WAVE / 2; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, BAMG_WAVE));
+        if (threadIdx.x == 0) mp = fmin(mp, v);
     }
 }
 
@@ -189,7 +208,6 @@ __global__ void __launch_bounds__(CZ_GJ_THREADS)
 k_gj_diag(int ld, int k0, int nb, double* __restrict__ A, const double* __restrict__ scale,
           double* __restrict__ minpiv) {
     __shared__ double prow[2][2][GJ_NB];
-    __shared__ double pcol[2][GJ_NB][2];
     const int w = threadIdx.x / BAMG_WAVE, c = threadIdx.x % BAMG_WAVE;
     double S[CZ_GJ_ROWS];
 #pragma unroll
@@ -198,7 +216,7 @@ k_gj_diag(int ld, int k0, int nb, double* __restrict__ A, const double* __restri
         S[i] = (r < nb && c < nb) ? A[(size_t)(k0 + r) * ld + k0 + c] : (r == c ? 1.0 : 0.0);
     }
     double mp = 1e300;
-    cz_gj(S, w, c, nb, *scale, mp, prow, pcol);
+    cz_gj(S, w, c, nb, *scale, mp, prow);
 #pragma unroll
     for (int i = 0; i < CZ_GJ_ROWS; ++i) {
         const int r = CZ_GJ_ROWS * w + i;
@@ -342,7 +360,6 @@ k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, 
     static_assert(CZ_GJ_THREADS == BAMG_BLK, "one workgroup size for both parts");
     __shared__ double lds[2 * GJ_NB * (GJ_NB + 2)];
     __shared__ __align__(16) double prow[2][2][GJ_NB];
-    __shared__ __align__(16) double pcol[2][GJ_NB][2];
     __shared__ double lob[GJ_NB][3];
     const CoarseDesc d = cd[blockIdx.y];
     const int K = d.nx - 1, q = blockIdx.x;
@@ -428,7 +445,7 @@ k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, 
         }
     }
     double mp = 1e300;
-    cz_gj(S, w, c, b, scale[blockIdx.y], mp, prow, pcol);
+    cz_gj(S, w, c, b, scale[blockIdx.y], mp, prow);
 #pragma unroll
     for (int i = 0; i < CZ_GJ_ROWS; ++i) {
         const int r = CZ_GJ_ROWS * w + i;
@@ -470,7 +487,6 @@ k_cz_lu_all(const CoarseDesc* __restrict__ cd, double* __restrict__ Fp, const do
     __shared__ double Ms[GJ_NB][GJ_NB + 1];
     __shared__ double Bs[GJ_NB][GJ_NB + 2];
     __shared__ __align__(16) double prow[2][2][GJ_NB];
-    __shared__ __align__(16) double pcol[2][GJ_NB][2];
     __shared__ double lob[GJ_NB][3];
     const CoarseDesc d = cd[blockIdx.x];
     if (d.n < 2 || (d.periodic && d.nx >= 3)) return;
@@ -526,7 +542,7 @@ k_cz_lu_all(const CoarseDesc* __restrict__ cd, double* __restrict__ Fp, const do
                 Dn[i] = (r < b && c < b) ? D1[r * b + c] : 0.0;
             }
         }
-        cz_gj(S, w, c, b, sc, mp, prow, pcol);
+        cz_gj(S, w, c, b, sc, mp, prow);
 #pragma unroll
         for (int i = 0; i < CZ_GJ_ROWS; ++i) {
             const int r = CZ_GJ_ROWS * w + i;

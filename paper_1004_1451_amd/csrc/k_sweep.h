@@ -156,6 +156,45 @@ template <> struct Ell4Val<double> {
     }
 };
 
+// Streaming forms of the accesses that touch each byte once (the ELL arrays,
+// D^-1 and the output): non-temporal, so that they do not displace the
+// neighbour rows of X from the caches.  Used where a row piece is 8 or 16
+// bytes; otherwise the plain forms.
+template <typename T, int VW>
+struct StreamIO {
+    static constexpr bool vec = (sizeof(T) * VW == 16 || sizeof(T) * VW == 8) && VW > 1;
+    static __device__ __forceinline__ void st(T* p, const T* x) {
+        if constexpr (vec) {
+            typedef T V __attribute__((ext_vector_type(VW)));
+            V v;
+#pragma unroll
+            for (int q = 0; q < VW; ++q) v[q] = x[q];
+            __builtin_nontemporal_store(v, (V*)p);
+        } else if constexpr (VW == 1) {
+            __builtin_nontemporal_store(x[0], p);
+        } else {
+            VecIO<T, VW>::st(p, x);
+        }
+    }
+};
+__device__ __forceinline__ int4 ld_nt_i4(const int* p) {
+    typedef int V __attribute__((ext_vector_type(4)));
+    const V v = __builtin_nontemporal_load((const V*)p);
+    return make_int4(v[0], v[1], v[2], v[3]);
+}
+template <typename M>
+__device__ __forceinline__ void ld_nt_w4(const M* p, M* w) {
+    typedef M V __attribute__((ext_vector_type(2)));
+    if constexpr (sizeof(M) == 4) {
+        typedef M V4 __attribute__((ext_vector_type(4)));
+        const V4 v = __builtin_nontemporal_load((const V4*)p);
+        w[0] = v[0]; w[1] = v[1]; w[2] = v[2]; w[3] = v[3];
+    } else {
+        const V a = __builtin_nontemporal_load((const V*)p), b = __builtin_nontemporal_load((const V*)p + 1);
+        w[0] = a[0]; w[1] = a[1]; w[2] = b[0]; w[3] = b[1];
+    }
+}
+
 template <typename T, typename M, int VW, int BS>
 __global__ void __launch_bounds__(BS)
 k_sweep_ve(int n, int G, FastDiv divG, const int* __restrict__ eci, const M* __restrict__ ev,
@@ -165,9 +204,9 @@ k_sweep_ve(int n, int G, FastDiv divG, const int* __restrict__ eci, const M* __r
     const int i = (int)divG.div((uint32_t)t), kg = t - i * G;
     const int R = G * VW;
     const size_t base = (size_t)i * R + (size_t)kg * VW;
-    const int4 c4 = *(const int4*)(eci + (size_t)i * 4);
+    const int4 c4 = ld_nt_i4(eci + (size_t)i * 4);
     M w[4];
-    Ell4Val<M>::ld(ev + (size_t)i * 4, w);
+    ld_nt_w4<M>(ev + (size_t)i * 4, w);
     T xt[VW], f[VW], acc[VW];
     VecIO<T, VW>::ld(X + base, xt);
     if (F) VecIO<T, VW>::ld(F + base, f);
@@ -176,7 +215,7 @@ k_sweep_ve(int n, int G, FastDiv divG, const int* __restrict__ eci, const M* __r
         for (int q = 0; q < VW; ++q) f[q] = (T)0;
 #pragma unroll
     for (int q = 0; q < VW; ++q) acc[q] = (T)0;
-    const T d = (T)dinv[i];
+    const T d = (T)__builtin_nontemporal_load(dinv + i);
     const int c[4] = {c4.x, c4.y, c4.z, c4.w};
     T x[4][VW];
 #pragma unroll
@@ -188,7 +227,7 @@ k_sweep_ve(int n, int G, FastDiv divG, const int* __restrict__ eci, const M* __r
     T y[VW];
 #pragma unroll
     for (int q = 0; q < VW; ++q) y[q] = xt[q] + d * (f[q] - acc[q]);
-    VecIO<T, VW>::st(Y + base, y);
+    StreamIO<T, VW>::st(Y + base, y);
 }
 
 // ELL-4 copy of a CSR matrix (see k_sweep_ve); err = 1 when a row has more
