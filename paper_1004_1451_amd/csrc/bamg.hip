@@ -742,7 +742,7 @@ struct Engine : bamg_ctx {
         for (double** p : {&ypool, &cpool, &bcolp, &t1, &t2, &rre, &rim}) *p = A.alloc<double>(NVt);
         gtpart = A.alloc<double>((size_t)ceil_div(maxnL, GT_RCH) * NVt);
         scale = A.alloc<double>(nch);
-        minpiv = A.alloc<double>(nch);
+        minpiv = A.alloc<double>(3 * (size_t)nch);   // per chain, then two half-factorisation partials
         cy = A.alloc<double>(nch);
         csc = A.alloc<double>((size_t)nch * SCS);
         const int am = std::max(1, AMmax);
@@ -1098,10 +1098,14 @@ struct Engine : bamg_ctx {
                 if (d.n < 2) continue;
                 if (d.periodic && d.nx >= 3) arrow = true; else plain = true;
             }
-            // chains without the arrow: the whole factorisation in one launch
-            if (plain)
-                hipLaunchKernelGGL(k_cz_lu_all, dim3(nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, Fp,
-                                   (const double*)scale, minpiv);
+            // chains without the arrow: the twisted factorisation, top and
+            // bottom halves at once, then the middle block row
+            if (plain) {
+                hipLaunchKernelGGL(k_cz_lu_half, dim3(2, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, Fp,
+                                   (const double*)scale, minpiv + nch);
+                hipLaunchKernelGGL(k_cz_lu_mid, dim3(nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, Fp,
+                                   (const double*)scale, (const double*)(minpiv + nch), minpiv);
+            }
             if (arrow) {
                 const dim3 gl(4, nch);
                 for (int k = 0; k + 1 < nxmax; ++k) {
@@ -1115,8 +1119,12 @@ struct Engine : bamg_ctx {
                                    (const double*)scale, minpiv, 1);
             }
             HIPCHK(hipGetLastError());
-            hipLaunchKernelGGL(k_cz_subst, dim3(ceil_div(maxnL, CZ_SUB_TC), nch), dim3(BAMG_BLK), 0, s,
-                               (const CoarseDesc*)cd, Wp, (const double*)Fp);
+            if (arrow)
+                hipLaunchKernelGGL(k_cz_subst, dim3(ceil_div(maxnL, CZ_SUB_TC), nch), dim3(BAMG_BLK), 0, s,
+                                   (const CoarseDesc*)cd, Wp, (const double*)Fp);
+            if (plain)
+                hipLaunchKernelGGL(k_cz_subst_tw, dim3(ceil_div(maxnL, CZ_SUB_TC), 2, nch), dim3(BAMG_BLK), 0, s,
+                                   (const CoarseDesc*)cd, Wp, (const double*)Fp);
             HIPCHK(hipGetLastError());
         }
         hipLaunchKernelGGL(k_cz_zero_border, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, Wp);

@@ -366,7 +366,7 @@ k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, 
     const int kk = k < 0 ? K : k;
     if (d.n < 2 || (k >= 0 && k >= K)) return;
     const bool arrow = d.periodic && d.nx >= 3;
-    if (arrow_only && !arrow) return;        // factored by k_cz_lu_all
+    if (arrow_only && !arrow) return;        // factored by k_cz_lu_half and k_cz_lu_mid
     if (q > 0) {
         if (arrow && kk >= 1)
             cz_elim_part(d, kk - 1, 1, q, Fp, (double(*)[GJ_NB + 2])lds, (double(*)[GJ_NB + 2])(lds + GJ_NB * (GJ_NB + 2)));
@@ -474,29 +474,45 @@ k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, 
     }
 }
 
-// The whole block LU of a chain without the arrow (non-periodic grid) in one
-// launch, one workgroup per chain (blockIdx.x): block row after block row the
-// same steps as k_cz_lu_step with identical arithmetic, the multiplier M_k
-// kept in LDS from the step that forms it to the step that uses it, and the
-// next diagonal block and bands loaded before the current Gauss-Jordan, so
-// their latency and the launch gaps between rows disappear.  Chains with the
-// arrow return at once (k_cz_lu_step with arrow_only takes them).
+// Twisted block factorisation of a chain without the arrow, two workgroups
+// per chain (grid (2, chains)) that run at the same time: with m = (K+1)/2,
+// workgroup 0 eliminates block rows 0 .. m-1 from the top,
+//   S_0 = D_0,  S_k = D_k - M_k U_{k-1},  M_{k+1} = L_{k+1} S_k^-1,
+// and workgroup 1 rows K .. m+1 from the bottom,
+//   R_K = D_K,  R_k = D_k - N_k L_{k+1},  N_{k-1} = U_{k-1} R_k^-1,
+// so the dependent chain of block inversions is half as long.  S_k^-1 and
+// R_k^-1 replace D_k; M_k (k = 1 .. m) replaces L_k, N_k (k = m .. K-1)
+// replaces U_k; the U_k above row m and the L_k below it stay as they are.
+// Products with the banded U and L take their 3 band terms in ascending
+// order; the multiplier being formed is kept in LDS for the next row, and the
+// next diagonal block is loaded before the current Gauss-Jordan.  Each
+// workgroup leaves its smallest pivot in mpart[2 c + half]; k_cz_lu_mid
+// inverts the middle block row.  Chains with the arrow return at once.
 __global__ void __launch_bounds__(BAMG_BLK)
-k_cz_lu_all(const CoarseDesc* __restrict__ cd, double* __restrict__ Fp, const double* __restrict__ scale,
-            double* __restrict__ minpiv) {
+k_cz_lu_half(const CoarseDesc* __restrict__ cd, double* __restrict__ Fp, const double* __restrict__ scale,
+             double* __restrict__ mpart) {
     __shared__ double Ms[GJ_NB][GJ_NB + 1];
     __shared__ double Bs[GJ_NB][GJ_NB + 2];
     __shared__ __align__(16) double prow[2][2][GJ_NB];
     __shared__ double lob[GJ_NB][3];
-    const CoarseDesc d = cd[blockIdx.x];
-    if (d.n < 2 || (d.periodic && d.nx >= 3)) return;
-    const int K = d.nx - 1, b = d.ny, tid = threadIdx.x;
-    const int c = tid % BAMG_WAVE, w = tid / BAMG_WAVE;
-    const double sc = scale[blockIdx.x];
+    const int ch = blockIdx.y, half = blockIdx.x;
+    const CoarseDesc d = cd[ch];
     double mp = 1e300;
+    if (d.n < 2 || (d.periodic && d.nx >= 3)) {
+        if (threadIdx.x == 0) mpart[2 * ch + half] = mp;
+        return;
+    }
+    const int K = d.nx - 1, m = (K + 1) / 2, b = d.ny, tid = threadIdx.x;
+    const int c = tid % BAMG_WAVE, w = tid / BAMG_WAVE;
+    const int first = half == 0 ? 0 : K, cnt = half == 0 ? m : K - m, step = half == 0 ? 1 : -1;
+    // the coupling to the previous row of the sequence (top: U_{k-1}; bottom:
+    // L_{k+1}) and the banded block the next multiplier comes from (top:
+    // L_{k+1} -> M_{k+1}; bottom: U_{k-1} -> N_{k-1})
+    const int pslot = half == 0 ? 1 : 2, nslot = half == 0 ? 2 : 1;
+    const double sc = scale[ch];
     double Dn[CZ_GJ_ROWS];
-    {
-        const double* D0 = cz_blk(Fp, d, 0, 0);
+    if (cnt > 0) {
+        const double* D0 = cz_blk(Fp, d, 0, first);
 #pragma unroll
         for (int i = 0; i < CZ_GJ_ROWS; ++i) {
             const int r = CZ_GJ_ROWS * w + i;
@@ -505,28 +521,28 @@ k_cz_lu_all(const CoarseDesc* __restrict__ cd, double* __restrict__ Fp, const do
     }
     int tc[3];
     cz_band(c, b, d.periodic, tc);
-    for (int kk = 0; kk <= K; ++kk) {
+    for (int it = 0; it < cnt; ++it) {
+        const int kk = first + step * it;
         double* D = cz_blk(Fp, d, 0, kk);
-        const bool mult = kk < K;
-        double* Lo1 = mult ? cz_blk(Fp, d, 2, kk + 1) : nullptr;
-        if (mult && tid < 3 * GJ_NB) {
+        double* Nx = cz_blk(Fp, d, nslot, kk + step);
+        if (tid < 3 * GJ_NB) {
             const int r = tid / 3, sl = tid % 3;
             int t[3];
             cz_band(r, b, d.periodic, t);
-            lob[r][sl] = (r < b && t[sl] >= 0) ? Lo1[r * b + t[sl]] : 0.0;
+            lob[r][sl] = (r < b && t[sl] >= 0) ? Nx[r * b + t[sl]] : 0.0;
         }
         double u[3] = {0.0, 0.0, 0.0};
-        if (kk >= 1) {
-            const double* Up = cz_blk(Fp, d, 1, kk - 1);
+        if (it >= 1) {
+            const double* Pv = cz_blk(Fp, d, pslot, kk - step);
 #pragma unroll
-            for (int sl = 0; sl < 3; ++sl) u[sl] = (c < b && tc[sl] >= 0) ? Up[tc[sl] * b + c] : 0.0;
+            for (int sl = 0; sl < 3; ++sl) u[sl] = (c < b && tc[sl] >= 0) ? Pv[tc[sl] * b + c] : 0.0;
         }
         double S[CZ_GJ_ROWS];
 #pragma unroll
         for (int i = 0; i < CZ_GJ_ROWS; ++i) {
             const int r = CZ_GJ_ROWS * w + i;
             double acc = 0.0;
-            if (kk >= 1) {
+            if (it >= 1) {
 #pragma unroll
                 for (int sl = 0; sl < 3; ++sl)
                     if (r < b && c < b && tc[sl] >= 0) acc = fma(Ms[r][tc[sl]], u[sl], acc);
@@ -534,8 +550,8 @@ k_cz_lu_all(const CoarseDesc* __restrict__ cd, double* __restrict__ Fp, const do
             S[i] = (r < b && c < b) ? Dn[i] - acc : (r == c ? 1.0 : 0.0);
         }
         // the next diagonal block, while this one is inverted
-        if (mult) {
-            const double* D1 = cz_blk(Fp, d, 0, kk + 1);
+        if (it + 1 < cnt) {
+            const double* D1 = cz_blk(Fp, d, 0, kk + step);
 #pragma unroll
             for (int i = 0; i < CZ_GJ_ROWS; ++i) {
                 const int r = CZ_GJ_ROWS * w + i;
@@ -548,38 +564,87 @@ k_cz_lu_all(const CoarseDesc* __restrict__ cd, double* __restrict__ Fp, const do
             const int r = CZ_GJ_ROWS * w + i;
             if (r < b && c < b) D[r * b + c] = S[i];
         }
-        if (mult) {
-            __syncthreads();
+        __syncthreads();
 #pragma unroll
-            for (int i = 0; i < CZ_GJ_ROWS; ++i) Bs[CZ_GJ_ROWS * w + i][c] = S[i];
-            __syncthreads();
+        for (int i = 0; i < CZ_GJ_ROWS; ++i) Bs[CZ_GJ_ROWS * w + i][c] = S[i];
+        __syncthreads();
 #pragma unroll
-            for (int i = 0; i < CZ_GJ_ROWS; ++i) {
-                const int r = CZ_GJ_ROWS * w + i;
-                if (!(r < b && c < b)) continue;
-                int t[3];
-                cz_band(r, b, d.periodic, t);
-                double acc = 0.0;
+        for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+            const int r = CZ_GJ_ROWS * w + i;
+            if (!(r < b && c < b)) continue;
+            int t[3];
+            cz_band(r, b, d.periodic, t);
+            double acc = 0.0;
 #pragma unroll
-                for (int sl = 0; sl < 3; ++sl)
-                    if (t[sl] >= 0) acc = fma(lob[r][sl], Bs[t[sl]][c], acc);
-                Lo1[r * b + c] = acc;
-                Ms[r][c] = acc;
-            }
-            __syncthreads();
+            for (int sl = 0; sl < 3; ++sl)
+                if (t[sl] >= 0) acc = fma(lob[r][sl], Bs[t[sl]][c], acc);
+            Nx[r * b + c] = acc;
+            Ms[r][c] = acc;
         }
+        __syncthreads();
     }
-    if (tid == 0) minpiv[blockIdx.x] = fmin(minpiv[blockIdx.x], mp);
+    if (tid == 0) mpart[2 * ch + half] = mp;
 }
 
-// All substitution steps of W = (L U)^-1 for one tile of CZ_SUB_TC columns
+// The middle block row of the twisted factorisation (one workgroup per
+// chain, after k_cz_lu_half):  Z = D_m - M_m U_{m-1} - N_m L_{m+1} (each
+// term present when its side has rows), Z^-1 replaces D_m; minpiv[c] takes
+// the smallest pivot of the three parts.
+__global__ void __launch_bounds__(BAMG_BLK)
+k_cz_lu_mid(const CoarseDesc* __restrict__ cd, double* __restrict__ Fp, const double* __restrict__ scale,
+            const double* __restrict__ mpart, double* __restrict__ minpiv) {
+    __shared__ __align__(16) double prow[2][2][GJ_NB];
+    const int ch = blockIdx.x;
+    const CoarseDesc d = cd[ch];
+    if (d.n < 2 || (d.periodic && d.nx >= 3)) return;
+    const int K = d.nx - 1, m = (K + 1) / 2, b = d.ny, tid = threadIdx.x;
+    const int c = tid % BAMG_WAVE, w = tid / BAMG_WAVE;
+    int tc[3];
+    cz_band(c, b, d.periodic, tc);
+    double* D = cz_blk(Fp, d, 0, m);
+    double S[CZ_GJ_ROWS];
+#pragma unroll
+    for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+        const int r = CZ_GJ_ROWS * w + i;
+        S[i] = (r < b && c < b) ? D[r * b + c] : (r == c ? 1.0 : 0.0);
+    }
+    for (int side = 0; side < 2; ++side) {
+        if (side == 0 ? m < 1 : m >= K) continue;
+        const double* Mm = cz_blk(Fp, d, side == 0 ? 2 : 1, m);           // M_m or N_m (dense)
+        const double* Pv = cz_blk(Fp, d, side == 0 ? 1 : 2, side == 0 ? m - 1 : m + 1);   // U_{m-1} or L_{m+1}
+        double u[3];
+#pragma unroll
+        for (int sl = 0; sl < 3; ++sl) u[sl] = (c < b && tc[sl] >= 0) ? Pv[tc[sl] * b + c] : 0.0;
+#pragma unroll
+        for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+            const int r = CZ_GJ_ROWS * w + i;
+            if (!(r < b && c < b)) continue;
+            double acc = 0.0;
+#pragma unroll
+            for (int sl = 0; sl < 3; ++sl)
+                if (tc[sl] >= 0) acc = fma(Mm[r * b + tc[sl]], u[sl], acc);
+            S[i] -= acc;
+        }
+    }
+    double mp = 1e300;
+    cz_gj(S, w, c, b, scale[ch], mp, prow);
+#pragma unroll
+    for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+        const int r = CZ_GJ_ROWS * w + i;
+        if (r < b && c < b) D[r * b + c] = S[i];
+    }
+    if (tid == 0) minpiv[ch] = fmin(minpiv[ch], fmin(mp, fmin(mpart[2 * ch], mpart[2 * ch + 1])));
+}
+
+// All substitution steps of W = (L U)^-1 for a chain with the arrow (the
+// others take k_cz_subst_tw), for one tile of CZ_SUB_TC columns
 // of one chain per workgroup (grid (ceil(n / CZ_SUB_TC), nch)): the columns of
 // W are independent right-hand sides (the identity), so a workgroup walks
 // every block row on its own, with the previous block row of the solution
 // kept in LDS.
 //   forward:  Y_0 = I_0;  Y_s = I_s - Lo_s Y_{s-1}  (s < K);
-//             Y_K = I_K - sum_{j < K-1} Rw_j Y_j - Lo_K Y_{K-1}  (arrow terms
-//             when periodic), in that order;
+//             Y_K = I_K - sum_{j < K-1} Rw_j Y_j - Lo_K Y_{K-1}  (the arrow
+//             terms), in that order;
 //   backward: X_K = Dinv_K Y_K;
 //             X_k = Dinv_k (Y_k - Up_k X_{k+1} - Cl_k X_K)  (k = K-1 .. 0).
 // Lo_s and Rw_j hold the multipliers (already times Dinv), Dk the inverted
@@ -611,20 +676,20 @@ __device__ __forceinline__ void cz_put(const double X[4], double (*Xs)[CZ_SUB_TC
     for (int a = 0; a < 4; ++a) Xs[tr + a][tc] = X[a];
 }
 
-// The blocks a substitution workgroup multiplies by, in the order it uses
-// them (index part * nx + k into the chain's block storage), for a tile whose
-// first identity block is s0.
-__device__ int cz_subst_sequence(int K, bool arrow, int s0, int* seq) {
+// The blocks a substitution workgroup of a chain with the arrow multiplies
+// by, in the order it uses them (index part * nx + k into the chain's block
+// storage), for a tile whose first identity block is s0.
+__device__ int cz_subst_sequence(int K, int s0, int* seq) {
     int m = 0;
     for (int s = s0; s < K; ++s) {
         if (s > s0) seq[m++] = 2 * (K + 1) + s;               // Lo_s
-        if (arrow && s < K - 1) seq[m++] = 4 * (K + 1) + s;   // Rw_s
+        if (s < K - 1) seq[m++] = 4 * (K + 1) + s;            // Rw_s
         if (s == K - 1) seq[m++] = 2 * (K + 1) + K;           // Lo_K
     }
     seq[m++] = K;                                              // Dinv_K
     for (int k = K - 1; k >= 0; --k) {
-        if (arrow) seq[m++] = (K + 1) + k;                     // Up_k (banded without the arrow: read directly)
-        if (arrow && k < K - 1) seq[m++] = 3 * (K + 1) + k;   // Cl_k
+        seq[m++] = (K + 1) + k;                                // Up_k
+        if (k < K - 1) seq[m++] = 3 * (K + 1) + k;            // Cl_k
         seq[m++] = k;                                          // Dinv_k
     }
     return m;
@@ -642,13 +707,14 @@ k_cz_subst(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const dou
     const int c0 = blockIdx.x * CZ_SUB_TC;
     if (n < 2 || c0 >= n) return;
     const bool arrow = d.periodic && d.nx >= 3;
+    if (!arrow) return;                              // k_cz_subst_tw takes those chains
     const double* F = Fp + d.boff;
     double* W = Wp + d.woff;
     const int w = min(CZ_SUB_TC, n - c0);
     const int s0 = c0 / b;
     const int tid = threadIdx.x, tr = (tid / CZ_SUB_TC) * 4, tc = tid % CZ_SUB_TC;
     const long long bb = (long long)b * b;
-    if (tid == 0) nseq = cz_subst_sequence(K, arrow, s0, seq);
+    if (tid == 0) nseq = cz_subst_sequence(K, s0, seq);
     __syncthreads();
     // The next block of the sequence is loaded into registers while the
     // current one is in use; next_block() moves it to Ms (the caller has
@@ -696,7 +762,7 @@ k_cz_subst(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const dou
         __syncthreads();
         cz_put(T, Xs, tr, tc);
         store(s, T);
-        if (arrow && s < K - 1) {
+        if (s < K - 1) {
             next_block();                            // Rw_s
             __syncthreads();
             cz_mac(b, Ms, Xs, tr, tc, TK, -1.0);
@@ -720,24 +786,7 @@ k_cz_subst(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const dou
     __syncthreads();
     cz_put(T, Ks, tr, tc);
     cz_put(T, Xs, tr, tc);                           // X_{k+1} for k = K-1
-    // backward substitution.  Without the arrow Up_k is banded (the 3 x 3
-    // box): its 3 band terms per row, in ascending column order, are read
-    // from memory (prefetched one step ahead) instead of staging the block.
-    double ub[4][3];
-    int tb[4][3];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) cz_band(tr + a, b, d.periodic, tb[a]);
-    auto load_band = [&](int k) {
-        const double* Up = F + (long long)((K + 1) + k) * bb;
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int sl = 0; sl < 3; ++sl) {
-                const int r = tr + a, t = tb[a][sl];
-                ub[a][sl] = (r < b && t >= 0) ? Up[r * b + t] : 0.0;
-            }
-    };
-    if (!arrow && K >= 1) load_band(K - 1);
+    // backward substitution
     for (int k = K - 1; k >= 0; --k) {
         double U[4];
 #pragma unroll
@@ -746,21 +795,10 @@ k_cz_subst(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const dou
             U[a] = (r < b && tc < w) ? W[(size_t)(k * b + r) * n + c0 + tc] : 0.0;
         }
         __syncthreads();
-        if (!arrow) {
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int sl = 0; sl < 3; ++sl) {
-                    const int t = tb[a][sl];
-                    if (tr + a < b && t >= 0) U[a] = fma(ub[a][sl], -1.0 * Xs[t][tc], U[a]);
-                }
-            if (k >= 1) load_band(k - 1);
-        } else {
-            next_block();                            // Up_k
-            __syncthreads();
-            cz_mac(b, Ms, Xs, tr, tc, U, -1.0);
-        }
-        if (arrow && k < K - 1) {
+        next_block();                                // Up_k
+        __syncthreads();
+        cz_mac(b, Ms, Xs, tr, tc, U, -1.0);
+        if (k < K - 1) {
             __syncthreads();
             next_block();                            // Cl_k
             __syncthreads();
@@ -768,6 +806,198 @@ k_cz_subst(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const dou
         }
         __syncthreads();
         next_block();                                // Dinv_k
+        cz_put(U, Xs, tr, tc);
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 4; ++a) T[a] = 0.0;
+        cz_mac(b, Ms, Xs, tr, tc, T, 1.0);
+        store(k, T);
+        __syncthreads();
+        cz_put(T, Xs, tr, tc);
+    }
+}
+
+// The substitution for chains without the arrow, on the twisted factors of
+// k_cz_lu_half / k_cz_lu_mid (m = (K+1)/2), for one tile of CZ_SUB_TC
+// columns of W per pair of workgroups (grid (tiles, 2, chains)):
+//   Y_s = I_s - M_s Y_{s-1}  (s = s0 .. m-1, Y = 0 above the tile's first
+//         identity block s0),
+//   V_s = I_s - N_s V_{s+1}  (s = s1 .. m+1, V = 0 below its last one s1),
+//   X_m = Z^-1 (I_m - M_m Y_{m-1} - N_m V_{m+1}),
+//   X_k = S_k^-1 (Y_k - U_k X_{k+1})  (k = m-1 .. 0; workgroup side 0),
+//   X_k = R_k^-1 (V_k - L_k X_{k-1})  (k = m+1 .. K; side 1).
+// Both workgroups of a tile form the forward parts and X_m; each stores and
+// finishes its own half of the block rows (side 0 also row m), so the chain
+// of dependent block products is about half that of one sweep over all rows.
+// The banded U_k and L_k take their 3 band terms per row in ascending column
+// order, read from memory one step ahead; every dense product adds over t in
+// ascending order.
+__device__ int cz_subst_tw_sequence(int K, int m, int s0, int s1, int side, int* seq) {
+    const bool top = s0 <= m - 1, bot = s1 >= m + 1;
+    int q = 0;
+    if (top)
+        for (int s = s0 + 1; s <= m - 1; ++s) seq[q++] = 2 * (K + 1) + s;       // M_s
+    if (bot)
+        for (int s = s1 - 1; s >= m + 1; --s) seq[q++] = (K + 1) + s;           // N_s
+    if (top) seq[q++] = 2 * (K + 1) + m;                                          // M_m
+    if (bot) seq[q++] = (K + 1) + m;                                              // N_m
+    seq[q++] = m;                                                                 // Z^-1
+    if (side == 0)
+        for (int k = m - 1; k >= 0; --k) seq[q++] = k;                            // S_k^-1
+    else
+        for (int k = m + 1; k <= K; ++k) seq[q++] = k;                            // R_k^-1
+    return q;
+}
+
+__global__ void __launch_bounds__(BAMG_BLK)
+k_cz_subst_tw(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const double* __restrict__ Fp) {
+    __shared__ double Ms[GJ_NB][GJ_NB + 1];
+    __shared__ double Xs[GJ_NB][CZ_SUB_TC + 1];
+    __shared__ double Ks[GJ_NB][CZ_SUB_TC + 1];
+    __shared__ int seq[2 * CZ_MAX_NX + 8];
+    __shared__ int nseq;
+    const CoarseDesc d = cd[blockIdx.z];
+    const int side = blockIdx.y;
+    const int K = d.nx - 1, b = d.ny, n = d.n, m = (K + 1) / 2;
+    const int c0 = blockIdx.x * CZ_SUB_TC;
+    if (n < 2 || c0 >= n || (d.periodic && d.nx >= 3)) return;
+    const double* F = Fp + d.boff;
+    double* W = Wp + d.woff;
+    const int w = min(CZ_SUB_TC, n - c0);
+    const int s0 = c0 / b, s1 = (c0 + w - 1) / b;
+    const bool top = s0 <= m - 1, bot = s1 >= m + 1;
+    const int tid = threadIdx.x, tr = (tid / CZ_SUB_TC) * 4, tc = tid % CZ_SUB_TC;
+    const long long bb = (long long)b * b;
+    if (tid == 0) nseq = cz_subst_tw_sequence(K, m, s0, s1, side, seq);
+    __syncthreads();
+    double pre[GJ_NB * GJ_NB / BAMG_BLK];
+    int sidx = 0;
+    auto fetch = [&](int i) {
+        const double* M = F + (long long)seq[i] * bb;
+#pragma unroll
+        for (int q = 0; q < GJ_NB * GJ_NB / BAMG_BLK; ++q) {
+            const int e = tid + q * BAMG_BLK, r = e / GJ_NB, c = e % GJ_NB;
+            pre[q] = (r < b && c < b) ? M[r * b + c] : 0.0;
+        }
+    };
+    auto next_block = [&]() {
+#pragma unroll
+        for (int q = 0; q < GJ_NB * GJ_NB / BAMG_BLK; ++q) {
+            const int e = tid + q * BAMG_BLK;
+            Ms[e / GJ_NB][e % GJ_NB] = pre[q];
+        }
+        if (++sidx < nseq) fetch(sidx);
+    };
+    fetch(0);
+    auto store = [&](int blk, const double X[4]) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int r = tr + a;
+            if (r < b && tc < w) W[(size_t)(blk * b + r) * n + c0 + tc] = X[a];
+        }
+    };
+    double T[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) T[a] = 0.0;
+    // rows of this side's half whose forward part is zero
+    if (side == 0)
+        for (int s = 0; s < min(s0, m); ++s) store(s, T);
+    else
+        for (int s = max(s1 + 1, m + 1); s <= K; ++s) store(s, T);
+    // forward from the top: Y_{m-1} ends in Ks
+    if (top) {
+        for (int s = s0; s <= m - 1; ++s) {
+            cz_ident(s, b, c0, w, tr, tc, T);
+            if (s > s0) {                            // Xs holds Y_{s-1}
+                __syncthreads();
+                next_block();                        // M_s
+                __syncthreads();
+                cz_mac(b, Ms, Xs, tr, tc, T, -1.0);
+            }
+            __syncthreads();
+            cz_put(T, Xs, tr, tc);
+            if (side == 0) store(s, T);
+        }
+        cz_put(T, Ks, tr, tc);
+    }
+    // forward from the bottom: V_{m+1} ends in Xs
+    if (bot) {
+        for (int s = s1; s >= m + 1; --s) {
+            cz_ident(s, b, c0, w, tr, tc, T);
+            if (s < s1) {                            // Xs holds V_{s+1}
+                __syncthreads();
+                next_block();                        // N_s
+                __syncthreads();
+                cz_mac(b, Ms, Xs, tr, tc, T, -1.0);
+            }
+            __syncthreads();
+            cz_put(T, Xs, tr, tc);
+            if (side == 1) store(s, T);
+        }
+    }
+    // middle block row
+    cz_ident(m, b, c0, w, tr, tc, T);
+    if (top) {
+        __syncthreads();
+        next_block();                                // M_m
+        __syncthreads();
+        cz_mac(b, Ms, Ks, tr, tc, T, -1.0);
+    }
+    if (bot) {
+        __syncthreads();
+        next_block();                                // N_m
+        __syncthreads();
+        cz_mac(b, Ms, Xs, tr, tc, T, -1.0);
+    }
+    __syncthreads();
+    next_block();                                    // Z^-1
+    cz_put(T, Xs, tr, tc);
+    __syncthreads();
+    double X[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) X[a] = 0.0;
+    cz_mac(b, Ms, Xs, tr, tc, X, 1.0);
+    if (side == 0) store(m, X);
+    __syncthreads();
+    cz_put(X, Xs, tr, tc);                           // X_m
+    // this side's half, outwards from row m; U_k (side 0) or L_k (side 1)
+    // banded, its 3 band terms per row read one step ahead
+    const int slot = side == 0 ? 1 : 2, dk = side == 0 ? -1 : 1;
+    const int kfirst = m + dk, cntk = side == 0 ? m : K - m;
+    double ub[4][3];
+    int tb[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) cz_band(tr + a, b, d.periodic, tb[a]);
+    auto load_band = [&](int k) {
+        const double* P = F + (long long)(slot * (K + 1) + k) * bb;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int sl = 0; sl < 3; ++sl) {
+                const int r = tr + a, t = tb[a][sl];
+                ub[a][sl] = (r < b && t >= 0) ? P[r * b + t] : 0.0;
+            }
+    };
+    if (cntk > 0) load_band(kfirst);
+    for (int it = 0; it < cntk; ++it) {
+        const int k = kfirst + dk * it;
+        double U[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int r = tr + a;
+            U[a] = (r < b && tc < w) ? W[(size_t)(k * b + r) * n + c0 + tc] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int sl = 0; sl < 3; ++sl) {
+                const int t = tb[a][sl];
+                if (tr + a < b && t >= 0) U[a] = fma(ub[a][sl], -1.0 * Xs[t][tc], U[a]);
+            }
+        if (it + 1 < cntk) load_band(k + dk);
+        __syncthreads();
+        next_block();                                // S_k^-1 or R_k^-1
         cz_put(U, Xs, tr, tc);
         __syncthreads();
 #pragma unroll
