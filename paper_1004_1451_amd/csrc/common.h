@@ -99,6 +99,23 @@ __device__ __forceinline__ T block_sum(T v, T* sh) {
     return s;
 }
 
+// 1/p from v_rcp_f64 refined by two Newton steps (within an ulp or so of the
+// rounded quotient, without the full division sequence).
+__device__ __forceinline__ double cz_recip(double p) {
+    double r = __builtin_amdgcn_rcp(p);
+    double e = fma(-p, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-p, r, 1.0);
+    return fma(r, e, r);
+}
+
+// Lane l's value of v (l uniform across the wave), without LDS.
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)u, l), hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __host__ __device__ __forceinline__ int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 // Several chains are handled as one block-diagonal system: on every level the

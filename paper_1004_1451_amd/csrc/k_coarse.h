@@ -120,26 +120,11 @@ __global__ void k_cz_extract(const CoarseDesc* __restrict__ cd, const double* __
 // Inversion of one diagonal block: Gauss-Jordan elimination without
 // pivoting on the block padded to 64 x 64 with the identity.  Thread (w, c)
 // of CZ_GJ_THREADS keeps column c of rows CZ_GJ_ROWS w .. + CZ_GJ_ROWS - 1 in
-// registers.  Before each step's barrier the owner wave puts the pivot rows,
-// and the lanes of the pivot columns in every wave their parts of those
-// columns, into LDS (two buffers, alternating).  1/p is v_rcp_f64 refined by
-// two Newton steps.
+// registers.  Before each step's barrier the owner wave puts the pivot rows
+// into LDS (two buffers, alternating).  1/p is v_rcp_f64 refined by two
+// Newton steps (cz_recip).
 #define CZ_GJ_THREADS 256
 #define CZ_GJ_ROWS (GJ_NB * BAMG_WAVE / CZ_GJ_THREADS)
-__device__ __forceinline__ double cz_recip(double p) {
-    double r = __builtin_amdgcn_rcp(p);
-    double e = fma(-p, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-p, r, 1.0);
-    return fma(r, e, r);
-}
-
-// Lane l's value of v (l uniform across the wave), without LDS.
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-    const long long u = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)u, l), hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 // Gauss-Jordan on the 64 x 64 block held in S by the CZ_GJ_THREADS threads
 // (w = wave, c = lane), two pivots per step: with the pivot block

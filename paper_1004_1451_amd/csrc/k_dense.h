@@ -548,21 +548,39 @@ __device__ void hqr_wave(int m, double* A, double* wr, double* wi, int* fail) {
                         w = -0.4375 * s * s;
                     }
                     ++its; ++its_total;
+                    // mm: the largest index in [l, nn-2] where the double
+                    // shift's first column makes the subdiagonal entry
+                    // (mm, mm-1) negligible (l when none does).  Each lane
+                    // evaluates its own candidate mm = lane, with the
+                    // arithmetic of a scan from nn-2 downwards; a ballot
+                    // takes the scan's first hit.
                     int mm;
-                    double p = 0, q = 0, r = 0, z;
-                    for (mm = nn - 2; mm >= l; --mm) {
-                        z = AA(mm, mm);
-                        r = x - z;
-                        double s = y - z;
-                        p = (r * s - w) / AA(mm + 1, mm) + AA(mm, mm + 1);
-                        q = AA(mm + 1, mm + 1) - z - r - s;
-                        r = AA(mm + 2, mm + 1);
-                        s = fabs(p) + fabs(q) + fabs(r);
-                        p /= s; q /= s; r /= s;
-                        if (mm == l) break;
-                        double u = fabs(AA(mm, mm - 1)) * (fabs(q) + fabs(r));
-                        double v = fabs(p) * (fabs(AA(mm - 1, mm - 1)) + fabs(z) + fabs(AA(mm + 1, mm + 1)));
-                        if (u <= eps * v) break;
+                    double p = 0, q = 0, r = 0;
+                    {
+                        bool ok = false;
+                        const int mc = lane;
+                        if (mc >= l && mc <= nn - 2) {
+                            const double z = AA(mc, mc);
+                            r = x - z;
+                            double s = y - z;
+                            p = (r * s - w) / AA(mc + 1, mc) + AA(mc, mc + 1);
+                            q = AA(mc + 1, mc + 1) - z - r - s;
+                            r = AA(mc + 2, mc + 1);
+                            s = fabs(p) + fabs(q) + fabs(r);
+                            p /= s; q /= s; r /= s;
+                            if (mc == l) {
+                                ok = true;
+                            } else {
+                                const double u = fabs(AA(mc, mc - 1)) * (fabs(q) + fabs(r));
+                                const double v = fabs(p) * (fabs(AA(mc - 1, mc - 1)) + fabs(z) + fabs(AA(mc + 1, mc + 1)));
+                                ok = u <= eps * v;
+                            }
+                        }
+                        const unsigned long long mk = __ballot(ok);
+                        mm = 63 - __clzll(mk);
+                        p = readlane_f64(p, mm);
+                        q = readlane_f64(q, mm);
+                        r = readlane_f64(r, mm);
                     }
                     lds_sync();
                     if (lane >= mm + 2 && lane <= nn) {
@@ -577,7 +595,7 @@ __device__ void hqr_wave(int m, double* A, double* wr, double* wi, int* fail) {
                             r = (k != nn - 1) ? AA(k + 2, k - 1) : 0.0;
                             x = fabs(p) + fabs(q) + fabs(r);
                             if (x == 0.0) continue;
-                            const double ix = 1.0 / x;
+                            const double ix = cz_recip(x);
                             p *= ix; q *= ix; r *= ix;
                         }
                         double s = sqrt(p * p + q * q + r * r);
@@ -591,7 +609,7 @@ __device__ void hqr_wave(int m, double* A, double* wr, double* wi, int* fail) {
                             }
                         }
                         p += s;
-                        const double is = 1.0 / s, ip = 1.0 / p;
+                        const double is = cz_recip(s), ip = cz_recip(p);
                         double hx = p * is, hy = q * is, hz = r * is;
                         double qq = q * ip, rr = r * ip;
                         lds_sync();
@@ -651,8 +669,8 @@ __device__ void hess_shift_factor_wave(int m, const double* __restrict__ H, doub
             nr = H[(size_t)(k + 1) * m + lane] - (lane == k + 1 ? thr : 0.0);
             ni = (lane == k + 1 ? -thi : 0.0);
         }
-        double ckr = __shfl(cr, k, BAMG_WAVE), cki = __shfl(ci, k, BAMG_WAVE);
-        double nkr = __shfl(nr, k, BAMG_WAVE), nki = __shfl(ni, k, BAMG_WAVE);
+        double ckr = readlane_f64(cr, k), cki = readlane_f64(ci, k);
+        double nkr = readlane_f64(nr, k), nki = readlane_f64(ni, k);
         const bool swap = nkr * nkr + nki * nki > ckr * ckr + cki * cki;
         if (swap) {
             double tr = cr, ti = ci; cr = nr; ci = ni; nr = tr; ni = ti;
@@ -662,8 +680,8 @@ __device__ void hess_shift_factor_wave(int m, const double* __restrict__ H, doub
             ckr = tiny; cki = 0.0;
             if (lane == k) { cr = tiny; ci = 0.0; }
         }
-        double d = ckr * ckr + cki * cki;
-        double fr = (nkr * ckr + nki * cki) / d, fi = (nki * ckr - nkr * cki) / d;
+        const double rd = cz_recip(ckr * ckr + cki * cki);
+        const double fr = (nkr * ckr + nki * cki) * rd, fi = (nki * ckr - nkr * cki) * rd;
         if (lane >= k && lane < m) {
             int e = upk(m, k, lane);
             U[2 * e] = cr; U[2 * e + 1] = ci;
@@ -677,7 +695,7 @@ __device__ void hess_shift_factor_wave(int m, const double* __restrict__ H, doub
     }
     {
         int k = m - 1;
-        double ckr = __shfl(cr, k, BAMG_WAVE), cki = __shfl(ci, k, BAMG_WAVE);
+        double ckr = readlane_f64(cr, k), cki = readlane_f64(ci, k);
         if (ckr * ckr + cki * cki < tiny * tiny) { ckr = tiny; cki = 0.0; }
         if (lane == k) { int e = upk(m, k, k); U[2 * e] = ckr; U[2 * e + 1] = cki; }
     }
@@ -686,43 +704,45 @@ __device__ void hess_shift_factor_wave(int m, const double* __restrict__ H, doub
 
 // z <- (H - theta I)^-1 z from the factors of hess_shift_factor_wave: the
 // recorded swaps and multipliers in step order, then back substitution.
+// Lane j keeps z_j in registers; each step broadcasts the entry it needs
+// with v_readlane, and the back substitution accumulates the sums of the
+// rows above column by column, so no step waits on a reduction.
 __device__ void hess_shift_apply_wave(int m, const double* U, const double* fm, const int* swp, double* zr,
                                       double* zi) {
     const int lane = threadIdx.x;
-    if (lane == 0) {
-        for (int k = 0; k < m - 1; ++k) {
-            if (swp[k]) {
-                double t0 = zr[k], t1 = zi[k];
-                zr[k] = zr[k + 1]; zi[k] = zi[k + 1]; zr[k + 1] = t0; zi[k + 1] = t1;
-            }
-            const double fr = fm[2 * k], fi = fm[2 * k + 1];
-            const double zkr = zr[k], zki = zi[k];
-            zr[k + 1] -= fr * zkr - fi * zki;
-            zi[k + 1] -= fr * zki + fi * zkr;
+    double vr = lane < m ? zr[lane] : 0.0, vi = lane < m ? zi[lane] : 0.0;
+    for (int k = 0; k < m - 1; ++k) {
+        const double akr = readlane_f64(vr, k), aki = readlane_f64(vi, k);
+        const double bkr = readlane_f64(vr, k + 1), bki = readlane_f64(vi, k + 1);
+        const bool sw = swp[k] != 0;
+        const double zkr = sw ? bkr : akr, zki = sw ? bki : aki;      // z_k after the swap
+        const double nkr = sw ? akr : bkr, nki = sw ? aki : bki;      // z_{k+1} after the swap
+        const double fr = fm[2 * k], fi = fm[2 * k + 1];
+        if (lane == k) { vr = zkr; vi = zki; }
+        if (lane == k + 1) {
+            vr = nkr - (fr * zkr - fi * zki);
+            vi = nki - (fr * zki + fi * zkr);
+        }
+    }
+    // back substitution: s_j accumulates sum_{t > j} U(j, t) z_t
+    double sr = 0.0, si = 0.0;
+    for (int i = m - 1; i >= 0; --i) {
+        const int e = upk(m, i, i);
+        const double ur = U[2 * e], ui = U[2 * e + 1];
+        const double ar = readlane_f64(vr - sr, i), ai = readlane_f64(vi - si, i);
+        const double rd = cz_recip(ur * ur + ui * ui);
+        const double xr = (ar * ur + ai * ui) * rd, xi = (ai * ur - ar * ui) * rd;
+        if (lane == i) { vr = xr; vi = xi; }
+        if (lane < i) {
+            const int f = upk(m, lane, i);
+            const double wr = U[2 * f], wi = U[2 * f + 1];
+            sr += wr * xr - wi * xi;
+            si += wr * xi + wi * xr;
         }
     }
     lds_sync();
-    for (int i = m - 1; i >= 0; --i) {
-        double sr = 0, si = 0;
-        if (lane > i && lane < m) {
-            int e = upk(m, i, lane);
-            double ur = U[2 * e], ui = U[2 * e + 1];
-            sr = ur * zr[lane] - ui * zi[lane];
-            si = ur * zi[lane] + ui * zr[lane];
-        }
-        sr = wave_sum(sr); si = wave_sum(si);
-        sr = __shfl(sr, 0, BAMG_WAVE); si = __shfl(si, 0, BAMG_WAVE);
-        lds_sync();
-        if (lane == 0) {
-            int e = upk(m, i, i);
-            double ur = U[2 * e], ui = U[2 * e + 1];
-            double ar = zr[i] - sr, ai = zi[i] - si;
-            double d = ur * ur + ui * ui;
-            zr[i] = (ar * ur + ai * ui) / d;
-            zi[i] = (ai * ur - ar * ui) / d;
-        }
-        lds_sync();
-    }
+    if (lane < m) { zr[lane] = vr; zi[lane] = vi; }
+    lds_sync();
 }
 
 // One wavefront: eigenvalues theta of H_m (Hessenberg, column-major (m+1) x m
