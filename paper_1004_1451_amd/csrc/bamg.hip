@@ -439,7 +439,7 @@ struct Engine : bamg_ctx {
     double *Vk = nullptr, *Zk = nullptr, *wk = nullptr, *Hg = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr,
            *ysol = nullptr, *hbuf = nullptr, *rvec = nullptr, *est = nullptr, *xperm = nullptr;
     int *act = nullptr, *kd = nullptr;
-    int* cmask = nullptr;            // chains the cycle works on (nch > 1; all ones outside solve)
+    int* cmask = nullptr;            // chains the cycle works on (all ones outside solve)
     int* hfail = nullptr;
     double *vin = nullptr, *vout = nullptr;   // permuted vectors of bamg_apply_vcycle
     // graph of one cycle on fixed buffers
@@ -455,8 +455,18 @@ struct Engine : bamg_ctx {
     // profiling
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_sweep, ev_gal, ev_ls, ev_gj;
     double gj_flops = 0;             // flops of the profiled dense updates
+    // FGMRES: chain flags after each Arnoldi step, read by the host one step
+    // late (pinned, two slots), the events that mark them, the inner
+    // tolerances on the device, and a row of ones to restore the cycle mask
+    int* hflag = nullptr;
+    hipEvent_t fev[2] = {nullptr, nullptr};
+    double* itol_d = nullptr;
+    int* ones_d = nullptr;
 
     ~Engine() override {
+        if (hflag) (void)hipHostFree(hflag);
+        for (hipEvent_t e : fev)
+            if (e) event_pool().put(e);
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cap_s) (void)hipStreamDestroy(cap_s);
@@ -660,9 +670,8 @@ struct Engine : bamg_ctx {
         zero(kind, sizeof(int) * nch * KV);
         zero(ent_col, sizeof(int) * nch * KV);
         x0 = A.alloc<double>(n);
-        if (nch > 1) {
-            cmask = A.upload(std::vector<int>(nch, 1));
-        }
+        cmask = A.upload(std::vector<int>(nch, 1));
+        ones_d = A.upload(std::vector<int>(nch, 1));
         {
             const size_t P = L[0].segp;
             size_t need = 4096;
@@ -2042,7 +2051,13 @@ struct Engine : bamg_ctx {
             gsaux = A.alloc<double>((size_t)nch * 3 * GS);
             gscoef = A.alloc<double>((size_t)nch * GS_CS);
             est = A.alloc<double>(nch);
-            act = cmask ? cmask : A.alloc<int>(nch);
+            act = cmask;
+            itol_d = A.alloc<double>(nch);
+            if (!hflag) {
+                HIPCHK(hipHostMalloc((void**)&hflag, sizeof(int) * 2 * nch, hipHostMallocDefault));
+                fev[0] = event_pool().get();
+                fev[1] = event_pool().get();
+            }
             kd = A.alloc<int>(nch);
             if (reordered) xperm = A.alloc<double>(N);
             m_alloc = m;
@@ -2064,7 +2079,7 @@ struct Engine : bamg_ctx {
         };
         normalise();
         const int nb = nblk(N);
-        std::vector<int> conv(nch, 0), hact(nch), hkd(nch);
+        std::vector<int> conv(nch, 0), hact(nch);
         std::vector<double> rel(nch, 0.0);
         if (flags & BAMG_PARNOLDI) {
             parnoldi_loop(xi, tol, max_cycles, inf);
@@ -2094,9 +2109,10 @@ struct Engine : bamg_ctx {
                     double r1 = h[(size_t)c * SCS + 1], x1 = h[(size_t)c * SCS + 2], b2 = h[(size_t)c * SCS + 3];
                     itol[c] = 0.5 * tol * x1 * std::sqrt(b2) / r1;
                     hact[c] = conv[c] ? 0 : 1;
-                    hkd[c] = 0;
                 }
                 HIPCHK(hipMemcpyAsync(act, hact.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
+                HIPCHK(hipMemcpyAsync(itol_d, itol.data(), sizeof(double) * nch, hipMemcpyHostToDevice, s));
+                zero(kd, sizeof(int) * nch);
                 zero(Hg, sizeof(double) * nch * HSg);
                 LAUNCH(k_seg_gmres_init, nch, 64, s, nch, m, (const double*)(sc + 3), SCS, g, GS);
                 LAUNCH(k_seg_scale, nb, BAMG_BLK, s, N, g0, nch, (const int*)nullptr, (const double*)rvec,
@@ -2127,28 +2143,39 @@ struct Engine : bamg_ctx {
                     hipLaunchKernelGGL(k_gs_final, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0,
                                        (const int*)act, (const double*)part, GS, hbuf, GS);
                     HIPCHK(hipGetLastError());
-                    LAUNCH(k_gs_step, ceil_div(nch, 64), 64, s, nch, j, ld, (const int*)act, (const double*)hbuf2,
-                           (const double*)hbuf, GS, Hg, HSg, cs, sn, g, gsaux, GS, gscoef, est);
-                    // |g_{j+1}| = 0 also covers a breakdown (||w|| = 0 gives s_j = 0)
-                    std::vector<double> e = getn(est, nch);
-                    bool any = false;
-                    for (int c = 0; c < nch; ++c) {
-                        if (!hact[c]) continue;
-                        hkd[c] = j + 1;
-                        if (e[c] <= itol[c] || e[c] == 0.0) hact[c] = 0;
-                        any |= (bool)hact[c];
+                    // the step also records kd = j + 1 and clears act[c] once the
+                    // estimate |g_{j+1}| reaches itol (or 0: a breakdown), on the
+                    // device, so every later kernel skips that chain
+                    LAUNCH(k_gs_step, ceil_div(nch, 64), 64, s, nch, j, ld, act, (const double*)hbuf2,
+                           (const double*)hbuf, GS, Hg, HSg, cs, sn, g, gsaux, GS, gscoef, est,
+                           (const double*)itol_d, kd);
+                    HIPCHK(hipMemcpyAsync(hflag + (j & 1) * nch, act, sizeof(int) * nch, hipMemcpyDeviceToHost, s));
+                    HIPCHK(hipEventRecord(fev[j & 1], s));
+                    const bool more = j + 1 < m && inf.cycles < max_cycles;
+                    if (more) {
+                        gs_dispatch(j, [&](auto kc) {
+                            hipLaunchKernelGGL(k_gs_update<decltype(kc)::value>, gsg, dim3(BAMG_BLK), 0, s, g0,
+                                               SEG_ROWS, vld, j, (const int*)act, Vk, (const double*)wk,
+                                               (const double*)gscoef, part, GS);
+                        });
+                        hipLaunchKernelGGL(k_gs_final, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0,
+                                           (const int*)act, (const double*)part, GS, hbuf2, GS);
+                        HIPCHK(hipGetLastError());
                     }
-                    if (!any || j + 1 >= m || inf.cycles >= max_cycles) break;
-                    HIPCHK(hipMemcpyAsync(act, hact.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
-                    gs_dispatch(j, [&](auto kc) {
-                        hipLaunchKernelGGL(k_gs_update<decltype(kc)::value>, gsg, dim3(BAMG_BLK), 0, s, g0, SEG_ROWS,
-                                           vld, j, (const int*)act, Vk, (const double*)wk, (const double*)gscoef, part, GS);
-                    });
-                    hipLaunchKernelGGL(k_gs_final, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0,
-                                       (const int*)act, (const double*)part, GS, hbuf2, GS);
-                    HIPCHK(hipGetLastError());
+                    // the flags of step j - 1, whose work finished while this
+                    // step's was queued: with no chain left, step j ran on
+                    // masked kernels only and does not count
+                    if (j >= 1) {
+                        HIPCHK(hipEventSynchronize(fev[(j - 1) & 1]));
+                        bool any = false;
+                        for (int c = 0; c < nch; ++c) {
+                            hact[c] = hflag[((j - 1) & 1) * nch + c];
+                            any |= (bool)hact[c];
+                        }
+                        if (!any) { --inf.cycles; break; }
+                    }
+                    if (!more) break;
                 }
-                HIPCHK(hipMemcpyAsync(kd, hkd.data(), sizeof(int) * nch, hipMemcpyHostToDevice, s));
                 LAUNCH(k_seg_gmres_y, ceil_div(nch, 64), 64, s, nch, ld, (const int*)kd, (const double*)Hg, HSg,
                        (const double*)g, GS, ysol);
                 LAUNCH(k_seg_xupdate, nb, BAMG_BLK, s, N, vld, g0, nch, (const int*)kd, (const double*)Zk,
@@ -2157,6 +2184,8 @@ struct Engine : bamg_ctx {
                 ++inf.restarts;
             }
         }
+        // the cycle works on every chain again outside the solve
+        HIPCHK(hipMemcpyAsync(cmask, ones_d, sizeof(int) * nch, hipMemcpyDeviceToDevice, s));
         // x >= 0, sum 1 per chain
         seg_reduce<RED_NEGSUM>(xi, nullptr, sc + 5);
         LAUNCH(k_clamp, nb, BAMG_BLK, s, N, xi);

@@ -443,10 +443,14 @@ __global__ void k_seg_scale(int N, const ChainGeo* __restrict__ geo, int nch, co
 //  3. The update pass's coefficients go to coef + c GS_CS.
 // alpha = 0 (v_j inside the span: a breakdown) empties column j and ends the
 // chain's inner iteration (est = 0, g_j = 0).
-__global__ void k_gs_step(int nch, int j, int ld, const int* __restrict__ act, const double* __restrict__ dvall,
+//  4. kd[c] = j + 1 (the columns the solution update takes), and act[c] = 0
+//     once est[c] <= itol[c] or est[c] = 0: the chain's inner iteration ends
+//     here and every later kernel of it skips the chain.
+__global__ void k_gs_step(int nch, int j, int ld, int* __restrict__ act, const double* __restrict__ dvall,
                           const double* __restrict__ dwall, int DS, double* __restrict__ Hall, int HS,
                           double* __restrict__ csall, double* __restrict__ snall, double* __restrict__ gall,
-                          double* __restrict__ auxall, int GS, double* __restrict__ coefall, double* __restrict__ est) {
+                          double* __restrict__ auxall, int GS, double* __restrict__ coefall, double* __restrict__ est,
+                          const double* __restrict__ itol, int* __restrict__ kd) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nch || !act[c]) return;
     const double* a = dvall + (size_t)c * DS;
@@ -511,11 +515,14 @@ __global__ void k_gs_step(int nch, int j, int ld, const int* __restrict__ act, c
     cs[j] = cc; sn[j] = ss;
     g[j + 1] = -ss * g[j];
     g[j] = cc * g[j];
-    est[c] = broke ? 0.0 : fabs(g[j + 1]);
+    const double e = broke ? 0.0 : fabs(g[j + 1]);
+    est[c] = e;
     for (int b = 0; b < j; ++b) { cf[b] = a[b]; cf[GS_MAXB + b] = d[b]; }
     cf[2 * GS_MAXB] = 1.0 / alpha;
     cf[2 * GS_MAXB + 1] = hj;
     cf[2 * GS_MAXB + 2] = nuj > 0.0 ? 1.0 / nuj : 0.0;
+    kd[c] = j + 1;
+    if (e <= itol[c] || e == 0.0) act[c] = 0;
 }
 
 // The same step for the multigrid-preconditioned Arnoldi method (Section
