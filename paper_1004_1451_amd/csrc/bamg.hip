@@ -412,7 +412,7 @@ struct Engine : bamg_ctx {
     double *Wp = nullptr, *Fp = nullptr, *ypool = nullptr, *cpool = nullptr, *bcolp = nullptr, *t1 = nullptr,
            *t2 = nullptr, *rre = nullptr, *rim = nullptr, *gtpart = nullptr;
     float* Wfp = nullptr;
-    double *scale = nullptr, *minpiv = nullptr, *cy = nullptr, *csc = nullptr, *dots = nullptr;
+    double *scale = nullptr, *minpiv = nullptr, *cy = nullptr, *csc = nullptr, *dots = nullptr, *vyb = nullptr;
     double *Vb = nullptr, *Hh = nullptr, *sel_lam = nullptr, *sel_s = nullptr;
     int* nsel = nullptr;
     int HS = 1, SS = 1, DS = 1;
@@ -764,6 +764,7 @@ struct Engine : bamg_ctx {
         sel_s = A.alloc<double>((size_t)nch * SS);
         nsel = A.alloc<int>((size_t)nch * NS);
         dots = A.alloc<double>((size_t)nch * DS);
+        vyb = A.alloc<double>((size_t)nch * DS);
     }
 
     // The coarsest descriptors after the coarsest operators moved (a level
@@ -1196,20 +1197,21 @@ struct Engine : bamg_ctx {
     // of classical Gram-Schmidt against columns 0..j, normalise (H[j+1, j]).
     void project_and_normalize(int j) {
         const dim3 gv(nblk(maxnL), nch);
-        hipLaunchKernelGGL(k_cz_arn_dots, dim3(1, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, 1,
+        // the projection against c with the first Gram-Schmidt pass, then the
+        // second pass, then the norm
+        hipLaunchKernelGGL(k_cz_arn_dots2, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j,
                            (const double*)cpool, (const double*)Vb, dots, DS);
-        hipLaunchKernelGGL(k_cz_arn_update, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, 0, (const double*)ypool,
-                           (const double*)cy, (const double*)dots, DS, Vb, Hh, HS);
+        hipLaunchKernelGGL(k_cz_arn_update2, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, (const double*)ypool,
+                           (const double*)cy, (const double*)dots, (const double*)vyb, DS, Vb, Hh, HS);
         if (j >= 0) {
-            for (int pass = 0; pass < 2; ++pass) {
-                hipLaunchKernelGGL(k_cz_arn_dots, dim3(j + 1, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, 0,
-                                   (const double*)cpool, (const double*)Vb, dots, DS);
-                hipLaunchKernelGGL(k_cz_arn_update, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, 1,
-                                   (const double*)ypool, (const double*)cy, (const double*)dots, DS, Vb, Hh, HS);
-            }
+            hipLaunchKernelGGL(k_cz_arn_dots, dim3(j + 1, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, 0,
+                               (const double*)cpool, (const double*)Vb, dots, DS);
+            hipLaunchKernelGGL(k_cz_arn_update, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, 1,
+                               (const double*)ypool, (const double*)cy, (const double*)dots, DS, Vb, Hh, HS);
         }
         HIPCHK(hipGetLastError());
-        LAUNCH(k_cz_arn_normalize, nch, BAMG_BLK, s, (const CoarseDesc*)cd, j, Vb, Hh, HS);
+        LAUNCH(k_cz_arn_normalize, nch, BAMG_BLK, s, (const CoarseDesc*)cd, j, Vb, Hh, HS, (const double*)ypool, vyb,
+               DS);
     }
 
     // ---- coarsest eigenpairs (Arnoldi, all chains in lockstep) ---------------

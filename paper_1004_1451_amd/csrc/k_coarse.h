@@ -1281,6 +1281,49 @@ __global__ void k_cz_arn_dots(const CoarseDesc* __restrict__ cd, int j, int with
     if (threadIdx.x == 0) dots[(size_t)blockIdx.y * DS + b] = s;
 }
 
+// The projection against c and the first Gram-Schmidt pass in one pair of
+// launches.  Dots pass (grid (j + 2, chains)): dots[0] = <c, u>, dots[1 + b]
+// = <v_b, u> (b <= j), each by one block in a fixed order.
+__global__ void k_cz_arn_dots2(const CoarseDesc* __restrict__ cd, int j, const double* __restrict__ cvec,
+                               const double* __restrict__ Vb, double* __restrict__ dots, int DS) {
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    const CoarseDesc d = cd[blockIdx.y];
+    const int b = blockIdx.x;
+    if (j >= d.am || b > j + 1) return;
+    const double* u = Vb + d.aoff + (size_t)(j + 1) * d.n;
+    const double* x = b == 0 ? cvec + d.voff : Vb + d.aoff + (size_t)(b - 1) * d.n;
+    double s = 0;
+    for (int i = threadIdx.x; i < d.n; i += BAMG_BLK) s += x[i] * u[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) dots[(size_t)blockIdx.y * DS + b] = s;
+}
+
+// Update of that pair: with a = <c, u> / cy, the projected u' = u - a y has
+// <v_b, u'> = <v_b, u> - a <v_b, y> (<v_b, y> = vy[b], kept from when v_b
+// was normalised), so u <- u - a y - sum_{b<=j} (<v_b, u> - a vy[b]) v_b and
+// H[0..j, j] += those coefficients (block 0).
+__global__ void k_cz_arn_update2(const CoarseDesc* __restrict__ cd, int j, const double* __restrict__ y,
+                                 const double* __restrict__ cy, const double* __restrict__ dots,
+                                 const double* __restrict__ vy, int DS, double* __restrict__ Vb,
+                                 double* __restrict__ H, int HS) {
+    __shared__ double cf[HQR_MAXM];
+    const CoarseDesc d = cd[blockIdx.y];
+    if (j >= d.am) return;
+    const double* dt = dots + (size_t)blockIdx.y * DS;
+    const double a = dt[0] / cy[blockIdx.y];
+    for (int b = threadIdx.x; b <= j; b += BAMG_BLK) cf[b] = dt[1 + b] - a * vy[(size_t)blockIdx.y * DS + b];
+    __syncthreads();
+    double* u = Vb + d.aoff + (size_t)(j + 1) * d.n;
+    for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < d.n; i += gridDim.x * BAMG_BLK) {
+        double s = u[i];
+        s -= y[d.voff + i] * a;
+        for (int b = 0; b <= j; ++b) s -= cf[b] * Vb[d.aoff + (size_t)b * d.n + i];
+        u[i] = s;
+    }
+    if (blockIdx.x == 0 && (int)threadIdx.x <= j)
+        H[(size_t)blockIdx.y * HS + (size_t)j * (d.am + 1) + threadIdx.x] += cf[threadIdx.x];
+}
+
 // mode 0: u -= y * dots[0] / cy;  mode 1: u -= sum_{b<=j} dots[b] v_b and
 // H[0..j, j] += dots (H: chain stride HS, column-major ld am+1).
 __global__ void k_cz_arn_update(const CoarseDesc* __restrict__ cd, int j, int mode, const double* __restrict__ y,
@@ -1304,9 +1347,11 @@ __global__ void k_cz_arn_update(const CoarseDesc* __restrict__ cd, int j, int mo
 }
 
 // Normalise basis column j+1 (or column 0 with j = -1): v = u / ||u||,
-// H[j+1, j] = ||u||.  One block per chain (fixed-order norm).
+// H[j+1, j] = ||u||, and vy[j+1] = <v, y> for the projections of later
+// steps.  One block per chain (fixed-order sums).
 __global__ void k_cz_arn_normalize(const CoarseDesc* __restrict__ cd, int j, double* __restrict__ Vb,
-                                   double* __restrict__ H, int HS) {
+                                   double* __restrict__ H, int HS, const double* __restrict__ y,
+                                   double* __restrict__ vy, int DS) {
     __shared__ double sh[BAMG_BLK / BAMG_WAVE];
     __shared__ double nrm;
     const CoarseDesc d = cd[blockIdx.x];
@@ -1320,7 +1365,14 @@ __global__ void k_cz_arn_normalize(const CoarseDesc* __restrict__ cd, int j, dou
         if (j >= 0) H[(size_t)blockIdx.x * HS + (size_t)j * (d.am + 1) + j + 1] = nrm;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < d.n; i += BAMG_BLK) u[i] = nrm > 0 ? u[i] / nrm : 0.0;
+    double t = 0;
+    for (int i = threadIdx.x; i < d.n; i += BAMG_BLK) {
+        const double v = nrm > 0 ? u[i] / nrm : 0.0;
+        u[i] = v;
+        t += v * y[d.voff + i];
+    }
+    t = block_sum(t, sh);
+    if (threadIdx.x == 0) vy[(size_t)blockIdx.x * DS + j + 1] = t;
 }
 
 // Ritz vector of entry e of chain (blockIdx.y): v = Vb[:, 0:am] s_e.
