@@ -991,8 +991,8 @@ struct Engine : bamg_ctx {
         auto part_k = r % 4 == 0 ? k_colnorm_partial<T, T, 4>
                     : r % 2 == 0 ? k_colnorm_partial<T, T, 2> : k_colnorm_partial<T, T, 1>;
         hipLaunchKernelGGL(part_k, grid, dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo, CN_ROWS, r, use_v,
-                           (const int*)nvc, VS, lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const T*)lv.U, (const T*)lv.V,
-                           WS, part);
+                           (const int*)nvc, VS, lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const int*)lv.B.eci,
+                           (const T*)lv.B.ev, (const T*)lv.U, (const T*)lv.V, WS, part);
         HIPCHK(hipGetLastError());
         dim3 g2(r + (use_v ? nvmax : 0), lv.ncont);
         hipLaunchKernelGGL(k_colnorm_final, g2, dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo, CN_ROWS, lv.cnp, r,
@@ -1288,22 +1288,23 @@ struct Engine : bamg_ctx {
                 if (mcgs) {      // in place, colour by colour
                     for (int cc = 0; cc < ncol; ++cc)
                         LAUNCH(relax, nblk(rows), BAMG_BLK, s, rows, (const ChainGeo*)lv.dgeo, lv.ncont,
-                               (const int*)nvc, KV, lv.B.rp, lv.B.ci, (const T*)lv.B.v, lv.Tm.rp, lv.Tm.ci,
-                               (const T*)lv.Tm.v, (const double*)lam, (const int*)kind, o.gs_omega, cc,
-                               (const T*)a, a);
+                               (const int*)nvc, KV, lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const int*)lv.B.eci,
+                               (const T*)lv.B.ev, lv.Tm.rp, lv.Tm.ci, (const T*)lv.Tm.v, (const double*)lam,
+                               (const int*)kind, o.gs_omega, cc, (const T*)a, a);
                     continue;
                 }
                 LAUNCH(relax, nblk(rows), BAMG_BLK, s, rows, (const ChainGeo*)lv.dgeo, lv.ncont, (const int*)nvc, KV,
-                       lv.B.rp, lv.B.ci, (const T*)lv.B.v, lv.Tm.rp, lv.Tm.ci, (const T*)lv.Tm.v, (const double*)lam,
-                       (const int*)kind, o.omega, -1, (const T*)a, b);
+                       lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const int*)lv.B.eci, (const T*)lv.B.ev, lv.Tm.rp, lv.Tm.ci,
+                       (const T*)lv.Tm.v, (const double*)lam, (const int*)kind, o.omega, -1, (const T*)a, b);
                 std::swap(a, b);
             }
             if (a != lv.V) HIPCHK(hipMemcpyAsync(lv.V, a, sizeof(T) * tot, hipMemcpyDeviceToDevice, s));
             if (nvmax > 1) {
                 hipLaunchKernelGGL((k_rayleigh_partial<T, T>), dim3(lv.cnp, lv.ncont), dim3(BAMG_BLK), 0, s,
                                    (const ChainGeo*)lv.dgeo, VS, KV, (const int*)nentc, (const int*)ent_col,
-                                   (const int*)kind, lv.B.rp, lv.B.ci, (const T*)lv.B.v, lv.Tm.rp, lv.Tm.ci,
-                                   (const T*)lv.Tm.v, (const T*)lv.V, CN_ROWS, part);
+                                   (const int*)kind, lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const int*)lv.B.eci,
+                                   (const T*)lv.B.ev, lv.Tm.rp, lv.Tm.ci, (const T*)lv.Tm.v, (const T*)lv.V, CN_ROWS,
+                                   part);
                 hipLaunchKernelGGL(k_rayleigh_final, dim3(KV, lv.ncont), dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo,
                                    CN_ROWS, lv.cnp, KV,
                                    (const int*)nentc, (const int*)ent_col, (const int*)kind, (const double*)part, lam);

@@ -512,6 +512,29 @@ __global__ void k_interp(int n, int R, FastDiv divR, const int* __restrict__ pc,
     Vf[t] = acc;
 }
 
+// Calls f(column, value) for the stored entries of row i in CSR order: from
+// the 4-wide ELL copy when one is given (eci non-null; its padding (i, 0)
+// is visited too and adds nothing to a sum), else from the CSR arrays.  The
+// ELL form needs no row pointer and moves a row's columns and values with
+// one 16-byte load each.
+template <typename M, typename F>
+__device__ __forceinline__ void row_entries(int i, const int* __restrict__ rp, const int* __restrict__ ci,
+                                            const M* __restrict__ v, const int* __restrict__ eci,
+                                            const M* __restrict__ ev, F&& f) {
+    if (eci) {
+        const int4 c4 = *(const int4*)(eci + (size_t)i * 4);
+        M w[4];
+        Ell4Val<M>::ld(ev + (size_t)i * 4, w);
+        f(c4.x, w[0]);
+        f(c4.y, w[1]);
+        f(c4.z, w[2]);
+        f(c4.w, w[3]);
+    } else {
+        const int p1 = rp[i + 1];
+        for (int p = rp[i]; p < p1; ++p) f(ci[p], v[p]);
+    }
+}
+
 // ---------------------------------------------------------------- TV weights
 // Stage 1, per chain (blockIdx.y) and row chunk of seg_rows (blockIdx.x):
 // partial sums of (B x_k)_i^2 and (x_k)_i^2 for the chain's columns k of
@@ -526,6 +549,7 @@ template <typename T, typename M, int VW>
 __global__ void __launch_bounds__(BAMG_BLK)
 k_colnorm_partial(const ChainGeo* __restrict__ geo, int seg_rows, int Ru, int use_v, const int* __restrict__ nvc,
                   int VS, const int* __restrict__ rp, const int* __restrict__ ci, const M* __restrict__ v,
+                  const int* __restrict__ eci, const M* __restrict__ ev,
                   const T* __restrict__ U, const T* __restrict__ V, int WS, double* __restrict__ part) {
     __shared__ double sr[BAMG_BLK * VW], sx[BAMG_BLK * VW];
     const int c = blockIdx.y;
@@ -545,14 +569,13 @@ k_colnorm_partial(const ChainGeo* __restrict__ geo, int seg_rows, int Ru, int us
             double acc[VW];
 #pragma unroll
             for (int q = 0; q < VW; ++q) acc[q] = 0.0;
-            const int p1 = rp[i + 1];
-            for (int p = rp[i]; p < p1; ++p) {
-                const double b = (double)v[p];
+            row_entries<M>(i, rp, ci, v, eci, ev, [&](int j, M bvj) {
+                const double b = (double)bvj;
                 T x[VW];
-                VecIO<T, VW>::ld(X + (size_t)ci[p] * ld + kx, x);
+                VecIO<T, VW>::ld(X + (size_t)j * ld + kx, x);
 #pragma unroll
                 for (int q = 0; q < VW; ++q) acc[q] += b * (double)x[q];
-            }
+            });
             T xi[VW];
             VecIO<T, VW>::ld(X + (size_t)i * ld + kx, xi);
 #pragma unroll
@@ -1161,6 +1184,7 @@ template <typename T, typename M, int VP>
 __global__ void __launch_bounds__(BAMG_BLK)
 k_eig_relax(int n, const ChainGeo* __restrict__ geo, int nch, const int* __restrict__ nvc, int KV,
             const int* __restrict__ brp, const int* __restrict__ bci, const M* __restrict__ bv,
+            const int* __restrict__ beci, const M* __restrict__ bev,
             const int* __restrict__ trp, const int* __restrict__ tci, const M* __restrict__ tv,
             const double* __restrict__ lamall, const int* __restrict__ kindall, double omega, int colour,
             const T* X, T* Y) {
@@ -1178,15 +1202,14 @@ k_eig_relax(int n, const ChainGeo* __restrict__ geo, int nch, const int* __restr
 #pragma unroll
     for (int c = 0; c < VP; ++c) { bs[c] = 0.0; ts[c] = 0.0; }
     double bd = 0, td = trp ? 0.0 : 1.0;
-    for (int p = brp[i]; p < brp[i + 1]; ++p) {
-        const int j = bci[p];
-        const double b = (double)bv[p];
-        if (j == i) bd = b;
+    row_entries<M>(i, brp, bci, bv, beci, bev, [&](int j, M bvj) {
+        const double b = (double)bvj;
+        if (j == i && b != 0.0) bd = b;        // not the ELL padding (i, 0)
         T x[VP];
         load(j, x);
 #pragma unroll
         for (int c = 0; c < VP; ++c) bs[c] += b * (double)x[c];
-    }
+    });
     T xo[VP];
     load(i, xo);
     if (trp) {
@@ -1244,6 +1267,7 @@ __global__ void __launch_bounds__(BAMG_BLK)
 k_rayleigh_partial(const ChainGeo* __restrict__ geo, int R, int KV, const int* __restrict__ nentc,
                    const int* __restrict__ ent_colall, const int* __restrict__ kindall,
                    const int* __restrict__ brp, const int* __restrict__ bci, const M* __restrict__ bv,
+                   const int* __restrict__ beci, const M* __restrict__ bev,
                    const int* __restrict__ trp, const int* __restrict__ tci, const M* __restrict__ tv,
                    const T* __restrict__ X, int seg_rows, double* __restrict__ part) {
     __shared__ double sh[4][BAMG_BLK];
@@ -1260,12 +1284,11 @@ k_rayleigh_partial(const ChainGeo* __restrict__ geo, int R, int KV, const int* _
         for (int i = r0 + dr; i < r1; i += rpp) {
             const double xr = (double)X[(size_t)i * R + c], xi = pair ? (double)X[(size_t)i * R + c + 1] : 0.0;
             double br = 0, bi = 0, tr = 0, ti = 0;
-            for (int p = brp[i]; p < brp[i + 1]; ++p) {
-                const int j = bci[p];
-                const double b = (double)bv[p];
+            row_entries<M>(i, brp, bci, bv, beci, bev, [&](int j, M bvj) {
+                const double b = (double)bvj;
                 br += b * (double)X[(size_t)j * R + c];
                 if (pair) bi += b * (double)X[(size_t)j * R + c + 1];
-            }
+            });
             if (trp) {
                 for (int p = trp[i]; p < trp[i + 1]; ++p) {
                     const int j = tci[p];
