@@ -1347,32 +1347,31 @@ __global__ void k_cz_arn_update(const CoarseDesc* __restrict__ cd, int j, int mo
 }
 
 // Normalise basis column j+1 (or column 0 with j = -1): v = u / ||u||,
-// H[j+1, j] = ||u||, and vy[j+1] = <v, y> for the projections of later
-// steps.  One block per chain (fixed-order sums).
+// H[j+1, j] = ||u||, and vy[j+1] = <v, y> = <u, y> / ||u|| (summed with the
+// norm) for the projections of later steps.  One block per chain
+// (fixed-order sums).
 __global__ void k_cz_arn_normalize(const CoarseDesc* __restrict__ cd, int j, double* __restrict__ Vb,
                                    double* __restrict__ H, int HS, const double* __restrict__ y,
                                    double* __restrict__ vy, int DS) {
-    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE], sh2[BAMG_BLK / BAMG_WAVE];
     __shared__ double nrm;
     const CoarseDesc d = cd[blockIdx.x];
     if (j >= d.am || d.am < 1) return;
     double* u = Vb + d.aoff + (size_t)(j + 1) * d.n;
-    double s = 0;
-    for (int i = threadIdx.x; i < d.n; i += BAMG_BLK) s += u[i] * u[i];
+    double s = 0, t = 0;
+    for (int i = threadIdx.x; i < d.n; i += BAMG_BLK) {
+        s += u[i] * u[i];
+        t += u[i] * y[d.voff + i];
+    }
     s = block_sum(s, sh);
+    t = block_sum(t, sh2);
     if (threadIdx.x == 0) {
         nrm = sqrt(s);
         if (j >= 0) H[(size_t)blockIdx.x * HS + (size_t)j * (d.am + 1) + j + 1] = nrm;
+        vy[(size_t)blockIdx.x * DS + j + 1] = nrm > 0 ? t / nrm : 0.0;
     }
     __syncthreads();
-    double t = 0;
-    for (int i = threadIdx.x; i < d.n; i += BAMG_BLK) {
-        const double v = nrm > 0 ? u[i] / nrm : 0.0;
-        u[i] = v;
-        t += v * y[d.voff + i];
-    }
-    t = block_sum(t, sh);
-    if (threadIdx.x == 0) vy[(size_t)blockIdx.x * DS + j + 1] = t;
+    for (int i = threadIdx.x; i < d.n; i += BAMG_BLK) u[i] = nrm > 0 ? u[i] / nrm : 0.0;
 }
 
 // Ritz vector of entry e of chain (blockIdx.y): v = Vb[:, 0:am] s_e.
