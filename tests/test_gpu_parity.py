@@ -165,6 +165,33 @@ def test_coarsest_matches_oracle(name, make, r, levels):
             assert np.abs(V[:, cc] - Vo[:, cc]).max() <= 1e-5, cc
 
 
+# Coarsest grids with few block rows: the two-sided block factorisation of
+# grids without the periodic arrow meets in block row m = (K + 1) / 2 of the
+# K + 1 rows, so one and two rows (no top or no bottom part), three rows and
+# rectangular blocks are the edge cases.
+SMALL_COARSEST = [
+    ("tandem2_2x2", lambda: C.tandem_queue(2), 2),
+    ("tandem4_3x3", lambda: C.tandem_queue(4), 2),
+    ("tandem4_2x2", lambda: C.tandem_queue(4), 3),
+    ("tandem8_5x5", lambda: C.tandem_queue(8), 2),
+    ("lattice7x13_4x7", lambda: C.weighted_lattice(7, seed=1, periodic=False, my=13), 2),
+    ("lattice2x20_1x10", lambda: C.weighted_lattice(2, seed=2, periodic=False, my=20), 2),
+]
+
+
+@pytest.mark.parametrize("name,make,levels", SMALL_COARSEST)
+def test_coarsest_inverse_small_grids(name, make, levels):
+    ch = make()
+    print(f"case {name}", flush=True)
+    h = B.Hierarchy.from_chain(ch, 4, B.default_options(levels=levels, stop_after=2))
+    L = levels - 1
+    BL = _csr(h, L, "B").toarray()
+    nL = BL.shape[0]
+    W = h.export(L, B.X_W).reshape(nL, nL)
+    Wo = O.coarsest_pinv(BL)
+    assert np.abs(W - Wo).max() <= 1e-8 * np.abs(Wo).max()
+
+
 @pytest.mark.parametrize("name,make,r,levels", CASES[:3])
 def test_upleg_matches_oracle(name, make, r, levels):
     ch = make()
