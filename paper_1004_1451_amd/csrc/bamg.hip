@@ -93,6 +93,15 @@ static int basis_stride(int n) {
     return (n + 31) / 32 * 32 + pad;
 }
 
+// Calls f(std::integral_constant<int, EF>) for the storage a setup kernel
+// reads B_l from (EF_CSR, EF_ELL4 or EF_ELL9).
+template <typename F>
+static void ef_dispatch(int ef, F&& f) {
+    if (ef == EF_ELL4) f(std::integral_constant<int, EF_ELL4>{});
+    else if (ef == EF_ELL9) f(std::integral_constant<int, EF_ELL9>{});
+    else f(std::integral_constant<int, EF_CSR>{});
+}
+
 // Calls f(std::integral_constant<int, K>) with K the multiple of 8 (8 .. 64)
 // that covers nb finished basis vectors: the register width of the
 // Gram-Schmidt passes.
@@ -984,15 +993,30 @@ struct Engine : bamg_ctx {
         if (a != X) HIPCHK(hipMemcpyAsync(X, a, sizeof(T) * tot, hipMemcpyDeviceToDevice, s));
     }
 
+    // The ELL copy of B_l that the setup kernels read instead of its CSR
+    // arrays: row-major 4-wide on the finest level, column-major 9-wide
+    // (stride = rows) on a coarse grid level, or none.
+    struct EllSrc { const int* c; const T* v; int ld; int ef; };
+    EllSrc ell_of(int l) const {
+        const auto& lv = L[l];
+        if (lv.B.eci) return {lv.B.eci, lv.B.ev, 0, EF_ELL4};
+        if (lv.B.cci) return {lv.B.cci, lv.B.cv, lv.rows, EF_ELL9};
+        return {nullptr, nullptr, 0, EF_CSR};
+    }
+
     // TV weights of the continuing chains of level l.
     void tv_weights(int l, int use_v) {
         auto& lv = L[l];
         dim3 grid(lv.cnp, lv.ncont);
-        auto part_k = r % 4 == 0 ? k_colnorm_partial<T, T, 4>
-                    : r % 2 == 0 ? k_colnorm_partial<T, T, 2> : k_colnorm_partial<T, T, 1>;
-        hipLaunchKernelGGL(part_k, grid, dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo, CN_ROWS, r, use_v,
-                           (const int*)nvc, VS, lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const int*)lv.B.eci,
-                           (const T*)lv.B.ev, (const T*)lv.U, (const T*)lv.V, WS, part);
+        const EllSrc es = ell_of(l);
+        ef_dispatch(es.ef, [&](auto efc) {
+            constexpr int EF = decltype(efc)::value;
+            auto part_k = r % 4 == 0 ? k_colnorm_partial<T, T, 4, EF>
+                        : r % 2 == 0 ? k_colnorm_partial<T, T, 2, EF> : k_colnorm_partial<T, T, 1, EF>;
+            hipLaunchKernelGGL(part_k, grid, dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo, CN_ROWS, r, use_v,
+                               (const int*)nvc, VS, lv.B.rp, lv.B.ci, (const T*)lv.B.v, es.c, es.v, es.ld,
+                               (const T*)lv.U, (const T*)lv.V, WS, part);
+        });
         HIPCHK(hipGetLastError());
         dim3 g2(r + (use_v ? nvmax : 0), lv.ncont);
         hipLaunchKernelGGL(k_colnorm_final, g2, dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo, CN_ROWS, lv.cnp, r,
@@ -1120,13 +1144,13 @@ struct Engine : bamg_ctx {
                 const dim3 gl(4, nch);
                 for (int k = 0; k + 1 < nxmax; ++k) {
                     hipLaunchKernelGGL(k_cz_lu_step, gl, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, k, Fp,
-                                       (const double*)scale, minpiv, 1);
+                                       (const double*)scale, minpiv);
                     hipLaunchKernelGGL(k_cz_elim_arrow, dim3(2, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, k,
                                        Fp);
                     HIPCHK(hipGetLastError());
                 }
                 hipLaunchKernelGGL(k_cz_lu_step, gl, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, -1, Fp,
-                                   (const double*)scale, minpiv, 1);
+                                   (const double*)scale, minpiv);
             }
             HIPCHK(hipGetLastError());
             if (arrow)
@@ -1278,33 +1302,40 @@ struct Engine : bamg_ctx {
             auto& c = L[l + 1];
             if (lv.ncont == 0) return;
             const int rows = lv.cont_rows;
+            const EllSrc es = ell_of(l);
             long long tot = (long long)rows * VS;
             FastDiv dR((uint32_t)VS);
             LAUNCH((k_interp<T, T>), nblk(tot), BAMG_BLK, s, rows, VS, dR, lv.pc, (const T*)lv.pv, (const T*)c.V, lv.V);
             T* a = lv.V;
             T* b = sweep_tmp;
-            auto relax = VS == 4 ? k_eig_relax<T, T, 4> : VS == 8 ? k_eig_relax<T, T, 8> : k_eig_relax<T, T, 12>;
-            for (int k = 0; k < o.nu_setup; ++k) {
-                if (mcgs) {      // in place, colour by colour
-                    for (int cc = 0; cc < ncol; ++cc)
-                        LAUNCH(relax, nblk(rows), BAMG_BLK, s, rows, (const ChainGeo*)lv.dgeo, lv.ncont,
-                               (const int*)nvc, KV, lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const int*)lv.B.eci,
-                               (const T*)lv.B.ev, lv.Tm.rp, lv.Tm.ci, (const T*)lv.Tm.v, (const double*)lam,
-                               (const int*)kind, o.gs_omega, cc, (const T*)a, a);
-                    continue;
+            ef_dispatch(es.ef, [&](auto efc) {
+                constexpr int EF = decltype(efc)::value;
+                auto relax = VS == 4 ? k_eig_relax<T, T, 4, EF>
+                           : VS == 8 ? k_eig_relax<T, T, 8, EF> : k_eig_relax<T, T, 12, EF>;
+                for (int k = 0; k < o.nu_setup; ++k) {
+                    if (mcgs) {      // in place, colour by colour
+                        for (int cc = 0; cc < ncol; ++cc)
+                            LAUNCH(relax, nblk(rows), BAMG_BLK, s, rows, (const ChainGeo*)lv.dgeo, lv.ncont,
+                                   (const int*)nvc, KV, lv.B.rp, lv.B.ci, (const T*)lv.B.v, es.c, es.v, es.ld,
+                                   lv.Tm.rp, lv.Tm.ci, (const T*)lv.Tm.v, (const double*)lam, (const int*)kind,
+                                   o.gs_omega, cc, (const T*)a, a);
+                        continue;
+                    }
+                    LAUNCH(relax, nblk(rows), BAMG_BLK, s, rows, (const ChainGeo*)lv.dgeo, lv.ncont, (const int*)nvc,
+                           KV, lv.B.rp, lv.B.ci, (const T*)lv.B.v, es.c, es.v, es.ld, lv.Tm.rp, lv.Tm.ci,
+                           (const T*)lv.Tm.v, (const double*)lam, (const int*)kind, o.omega, -1, (const T*)a, b);
+                    std::swap(a, b);
                 }
-                LAUNCH(relax, nblk(rows), BAMG_BLK, s, rows, (const ChainGeo*)lv.dgeo, lv.ncont, (const int*)nvc, KV,
-                       lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const int*)lv.B.eci, (const T*)lv.B.ev, lv.Tm.rp, lv.Tm.ci,
-                       (const T*)lv.Tm.v, (const double*)lam, (const int*)kind, o.omega, -1, (const T*)a, b);
-                std::swap(a, b);
-            }
+            });
             if (a != lv.V) HIPCHK(hipMemcpyAsync(lv.V, a, sizeof(T) * tot, hipMemcpyDeviceToDevice, s));
             if (nvmax > 1) {
-                hipLaunchKernelGGL((k_rayleigh_partial<T, T>), dim3(lv.cnp, lv.ncont), dim3(BAMG_BLK), 0, s,
-                                   (const ChainGeo*)lv.dgeo, VS, KV, (const int*)nentc, (const int*)ent_col,
-                                   (const int*)kind, lv.B.rp, lv.B.ci, (const T*)lv.B.v, (const int*)lv.B.eci,
-                                   (const T*)lv.B.ev, lv.Tm.rp, lv.Tm.ci, (const T*)lv.Tm.v, (const T*)lv.V, CN_ROWS,
-                                   part);
+                ef_dispatch(es.ef, [&](auto efc) {
+                    hipLaunchKernelGGL((k_rayleigh_partial<T, T, decltype(efc)::value>), dim3(lv.cnp, lv.ncont),
+                                       dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo, VS, KV, (const int*)nentc,
+                                       (const int*)ent_col, (const int*)kind, lv.B.rp, lv.B.ci, (const T*)lv.B.v, es.c,
+                                       es.v, es.ld, lv.Tm.rp, lv.Tm.ci, (const T*)lv.Tm.v, (const T*)lv.V, CN_ROWS,
+                                       part);
+                });
                 hipLaunchKernelGGL(k_rayleigh_final, dim3(KV, lv.ncont), dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo,
                                    CN_ROWS, lv.cnp, KV,
                                    (const int*)nentc, (const int*)ent_col, (const int*)kind, (const double*)part, lam);

@@ -311,13 +311,12 @@ k_cz_elim_arrow(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ F
     cz_elim_part(d, k, 0, blockIdx.x, Fp, AsT, Bs);
 }
 
-// Step k of the block LU for every chain (k < 0: the chain's last block K),
-// grid (1 or 4, nch).  Workgroup 0 forms D_k - Lo_k Up_{k-1} (the update of
-// step k-1, summed as cz_gemm does) in the Gauss-Jordan registers, inverts
-// it, stores Dinv_k and, for chains without the periodic arrow, the
-// multipliers Lo_{k+1} = Lo_{k+1} Dinv_k from the same registers.  For the
-// periodic chains, workgroups 1..3 do the other updates of step k-1, which
-// touch none of the blocks workgroup 0 reads or writes, and their
+// Step k of the block LU for every chain with the periodic arrow (k < 0:
+// the chain's last block K), grid (4, nch); the other chains take the
+// twisted factorisation.  Workgroup 0 forms D_k - Lo_k Up_{k-1} (the update
+// of step k-1, summed as cz_gemm does) in the Gauss-Jordan registers,
+// inverts it and stores Dinv_k; workgroups 1..3 do the other updates of step
+// k-1, which touch none of the blocks workgroup 0 reads or writes, and the
 // multipliers follow in k_cz_elim_arrow.  One launch per block row instead
 // of three.
 // Columns t of row j of a block that couples two grid rows of the coarsest
@@ -341,19 +340,17 @@ __device__ __forceinline__ void cz_band(int j, int b, int periodic, int (&t)[3])
 
 __global__ void __launch_bounds__(BAMG_BLK)
 k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, const double* __restrict__ scale,
-             double* __restrict__ minpiv, int arrow_only) {
+             double* __restrict__ minpiv) {
     static_assert(CZ_GJ_THREADS == BAMG_BLK, "one workgroup size for both parts");
     __shared__ double lds[2 * GJ_NB * (GJ_NB + 2)];
     __shared__ __align__(16) double prow[2][2][GJ_NB];
-    __shared__ double lob[GJ_NB][3];
     const CoarseDesc d = cd[blockIdx.y];
     const int K = d.nx - 1, q = blockIdx.x;
     const int kk = k < 0 ? K : k;
     if (d.n < 2 || (k >= 0 && k >= K)) return;
-    const bool arrow = d.periodic && d.nx >= 3;
-    if (arrow_only && !arrow) return;        // factored by k_cz_lu_half and k_cz_lu_mid
+    if (!(d.periodic && d.nx >= 3)) return;  // factored by k_cz_lu_half and k_cz_lu_mid
     if (q > 0) {
-        if (arrow && kk >= 1)
+        if (kk >= 1)
             cz_elim_part(d, kk - 1, 1, q, Fp, (double(*)[GJ_NB + 2])lds, (double(*)[GJ_NB + 2])(lds + GJ_NB * (GJ_NB + 2)));
         return;
     }
@@ -361,29 +358,17 @@ k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, 
     const int b = d.ny, tid = threadIdx.x;
     const int c = tid % BAMG_WAVE, w = tid / BAMG_WAVE;
     double* D = cz_blk(Fp, d, 0, kk);
-    // the diagonal block and the band of the next multiplier block are read
-    // at once, so their latency hides behind the first product
-    const bool mult = !arrow && kk < K;
-    double* Lo1 = mult ? cz_blk(Fp, d, 2, kk + 1) : nullptr;
     double Dv[CZ_GJ_ROWS];
 #pragma unroll
     for (int i = 0; i < CZ_GJ_ROWS; ++i) {
         const int r = CZ_GJ_ROWS * w + i;
         Dv[i] = (r < b && c < b) ? D[r * b + c] : 0.0;
     }
-    // band of Lo_{k+1}: lob[r][s] = Lo[r][t_s], t_0 < t_1 < t_2 the columns of
-    // cz_band(r) (Lo couples grid rows k+1 and k within the 3 x 3 box)
-    if (mult && tid < 3 * GJ_NB) {
-        const int r = tid / 3, sl = tid % 3;
-        int t[3];
-        cz_band(r, b, d.periodic, t);
-        lob[r][sl] = (r < b && t[sl] >= 0) ? Lo1[r * b + t[sl]] : 0.0;
-    }
     double S[CZ_GJ_ROWS];
-    if (kk >= 1 && arrow) {
-        // periodic chains: the arrow elimination fills the block that couples
-        // the last two grid rows, so the product stays dense (4 x 4 tiles,
-        // then through LDS into this thread's column strip)
+    if (kk >= 1) {
+        // the arrow elimination fills the block that couples the last two
+        // grid rows, so the product stays dense (4 x 4 tiles, then through
+        // LDS into this thread's column strip)
         double (*AsT)[GJ_NB + 2] = (double(*)[GJ_NB + 2])lds;
         const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
         cz_stage(b, cz_blk(Fp, d, 2, kk), AsT, cz_blk(Fp, d, 1, kk - 1), Bs);
@@ -401,27 +386,6 @@ k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, 
             const int r = CZ_GJ_ROWS * w + i;
             S[i] = (r < b && c < b) ? Dv[i] - AsT[r][c] : (r == c ? 1.0 : 0.0);
         }
-    } else if (kk >= 1) {
-        // S = D_k - M_k Up_{k-1}: Up_{k-1} is banded (never updated without
-        // the arrow), so column c of the product takes the columns
-        // cz_band(c) of M_k, in ascending order (the order of the dense sum,
-        // whose other terms add exact zeros)
-        const double* M = cz_blk(Fp, d, 2, kk);
-        const double* Up = cz_blk(Fp, d, 1, kk - 1);
-        int t[3];
-        cz_band(c, b, d.periodic, t);
-        double u[3];
-#pragma unroll
-        for (int sl = 0; sl < 3; ++sl) u[sl] = (c < b && t[sl] >= 0) ? Up[t[sl] * b + c] : 0.0;
-#pragma unroll
-        for (int i = 0; i < CZ_GJ_ROWS; ++i) {
-            const int r = CZ_GJ_ROWS * w + i;
-            double acc = 0.0;
-#pragma unroll
-            for (int sl = 0; sl < 3; ++sl)
-                if (r < b && c < b && t[sl] >= 0) acc = fma(M[r * b + t[sl]], u[sl], acc);
-            S[i] = (r < b && c < b) ? Dv[i] - acc : (r == c ? 1.0 : 0.0);
-        }
     } else {
 #pragma unroll
         for (int i = 0; i < CZ_GJ_ROWS; ++i) {
@@ -437,26 +401,6 @@ k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, 
         if (r < b && c < b) D[r * b + c] = S[i];
     }
     if (tid == 0) minpiv[blockIdx.y] = fmin(minpiv[blockIdx.y], mp);
-    if (mult) {
-        // M_{k+1} = Lo_{k+1} Dinv_k: row r takes the rows cz_band(r) of Dinv_k
-        // (its column c through LDS), in ascending order
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < CZ_GJ_ROWS; ++i) Bs[CZ_GJ_ROWS * w + i][c] = S[i];
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < CZ_GJ_ROWS; ++i) {
-            const int r = CZ_GJ_ROWS * w + i;
-            if (!(r < b && c < b)) continue;
-            int t[3];
-            cz_band(r, b, d.periodic, t);
-            double acc = 0.0;
-#pragma unroll
-            for (int sl = 0; sl < 3; ++sl)
-                if (t[sl] >= 0) acc = fma(lob[r][sl], Bs[t[sl]][c], acc);
-            Lo1[r * b + c] = acc;
-        }
-    }
 }
 
 // Twisted block factorisation of a chain without the arrow, two workgroups

@@ -512,16 +512,27 @@ __global__ void k_interp(int n, int R, FastDiv divR, const int* __restrict__ pc,
     Vf[t] = acc;
 }
 
-// Calls f(column, value) for the stored entries of row i in CSR order: from
-// the 4-wide ELL copy when one is given (eci non-null; its padding (i, 0)
-// is visited too and adds nothing to a sum), else from the CSR arrays.  The
-// ELL form needs no row pointer and moves a row's columns and values with
-// one 16-byte load each.
-template <typename M, typename F>
+// Calls f(column, value) for the stored entries of row i in CSR order, from
+// the storage EF names: EF_ELL4 the row-major 4-wide copy of the finest
+// level (a row's columns and values move with one 16-byte load each),
+// EF_ELL9 the column-major 9-wide copy of a coarse grid level (slot k of row
+// i at k * eld + i), EF_CSR the CSR arrays.  An ELL copy's padding (i, 0) is
+// visited too and adds nothing to a sum.
+#define EF_CSR 0
+#define EF_ELL4 4
+#define EF_ELL9 9
+template <int EF, typename M, typename F>
 __device__ __forceinline__ void row_entries(int i, const int* __restrict__ rp, const int* __restrict__ ci,
                                             const M* __restrict__ v, const int* __restrict__ eci,
-                                            const M* __restrict__ ev, F&& f) {
-    if (eci) {
+                                            const M* __restrict__ ev, int eld, F&& f) {
+    if constexpr (EF == EF_ELL9) {
+        int c[9];
+        M w[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) { c[k] = eci[(size_t)k * eld + i]; w[k] = ev[(size_t)k * eld + i]; }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) f(c[k], w[k]);
+    } else if constexpr (EF == EF_ELL4) {
         const int4 c4 = *(const int4*)(eci + (size_t)i * 4);
         M w[4];
         Ell4Val<M>::ld(ev + (size_t)i * 4, w);
@@ -545,11 +556,11 @@ __device__ __forceinline__ void row_entries(int i, const int* __restrict__ rp, c
 // then, per column, one thread adds the per-thread sums in row order.
 // part[((c 2 WS) + k) P + chunk] = sum of (B x_k)^2, [.. + WS + k ..] = sum
 // of x_k^2 (P = chunks per chain slot), for the chain's used columns only.
-template <typename T, typename M, int VW>
+template <typename T, typename M, int VW, int EF>
 __global__ void __launch_bounds__(BAMG_BLK)
 k_colnorm_partial(const ChainGeo* __restrict__ geo, int seg_rows, int Ru, int use_v, const int* __restrict__ nvc,
                   int VS, const int* __restrict__ rp, const int* __restrict__ ci, const M* __restrict__ v,
-                  const int* __restrict__ eci, const M* __restrict__ ev,
+                  const int* __restrict__ eci, const M* __restrict__ ev, int eld,
                   const T* __restrict__ U, const T* __restrict__ V, int WS, double* __restrict__ part) {
     __shared__ double sr[BAMG_BLK * VW], sx[BAMG_BLK * VW];
     const int c = blockIdx.y;
@@ -569,7 +580,7 @@ k_colnorm_partial(const ChainGeo* __restrict__ geo, int seg_rows, int Ru, int us
             double acc[VW];
 #pragma unroll
             for (int q = 0; q < VW; ++q) acc[q] = 0.0;
-            row_entries<M>(i, rp, ci, v, eci, ev, [&](int j, M bvj) {
+            row_entries<EF, M>(i, rp, ci, v, eci, ev, eld, [&](int j, M bvj) {
                 const double b = (double)bvj;
                 T x[VW];
                 VecIO<T, VW>::ld(X + (size_t)j * ld + kx, x);
@@ -1180,11 +1191,11 @@ k_galerkin_numeric(int nc, const ChainGeo* __restrict__ geoc, int nch,
 // Column 0 (the null-vector approximation) has lam = 0.  Products are added
 // in CSR order in FP64.  colour >= 0: one colour of a multicolour
 // Gauss-Seidel sweep (k_mcgs.h), in place (Y == X), other rows untouched.
-template <typename T, typename M, int VP>
+template <typename T, typename M, int VP, int EF>
 __global__ void __launch_bounds__(BAMG_BLK)
 k_eig_relax(int n, const ChainGeo* __restrict__ geo, int nch, const int* __restrict__ nvc, int KV,
             const int* __restrict__ brp, const int* __restrict__ bci, const M* __restrict__ bv,
-            const int* __restrict__ beci, const M* __restrict__ bev,
+            const int* __restrict__ beci, const M* __restrict__ bev, int beld,
             const int* __restrict__ trp, const int* __restrict__ tci, const M* __restrict__ tv,
             const double* __restrict__ lamall, const int* __restrict__ kindall, double omega, int colour,
             const T* X, T* Y) {
@@ -1202,7 +1213,7 @@ k_eig_relax(int n, const ChainGeo* __restrict__ geo, int nch, const int* __restr
 #pragma unroll
     for (int c = 0; c < VP; ++c) { bs[c] = 0.0; ts[c] = 0.0; }
     double bd = 0, td = trp ? 0.0 : 1.0;
-    row_entries<M>(i, brp, bci, bv, beci, bev, [&](int j, M bvj) {
+    row_entries<EF, M>(i, brp, bci, bv, beci, bev, beld, [&](int j, M bvj) {
         const double b = (double)bvj;
         if (j == i && b != 0.0) bd = b;        // not the ELL padding (i, 0)
         T x[VP];
@@ -1262,12 +1273,12 @@ k_eig_relax(int n, const ChainGeo* __restrict__ geo, int nch, const int* __restr
 // two) the sums x^H B x and x^H T x (re, im).  Thread layout: nent slots per
 // row (thread t: row t / nent, entry t % nent), then one thread per entry adds
 // the per-thread sums in thread order -> part[chain][chunk][entry][4].
-template <typename T, typename M>
+template <typename T, typename M, int EF>
 __global__ void __launch_bounds__(BAMG_BLK)
 k_rayleigh_partial(const ChainGeo* __restrict__ geo, int R, int KV, const int* __restrict__ nentc,
                    const int* __restrict__ ent_colall, const int* __restrict__ kindall,
                    const int* __restrict__ brp, const int* __restrict__ bci, const M* __restrict__ bv,
-                   const int* __restrict__ beci, const M* __restrict__ bev,
+                   const int* __restrict__ beci, const M* __restrict__ bev, int beld,
                    const int* __restrict__ trp, const int* __restrict__ tci, const M* __restrict__ tv,
                    const T* __restrict__ X, int seg_rows, double* __restrict__ part) {
     __shared__ double sh[4][BAMG_BLK];
@@ -1284,7 +1295,7 @@ k_rayleigh_partial(const ChainGeo* __restrict__ geo, int R, int KV, const int* _
         for (int i = r0 + dr; i < r1; i += rpp) {
             const double xr = (double)X[(size_t)i * R + c], xi = pair ? (double)X[(size_t)i * R + c + 1] : 0.0;
             double br = 0, bi = 0, tr = 0, ti = 0;
-            row_entries<M>(i, brp, bci, bv, beci, bev, [&](int j, M bvj) {
+            row_entries<EF, M>(i, brp, bci, bv, beci, bev, beld, [&](int j, M bvj) {
                 const double b = (double)bvj;
                 br += b * (double)X[(size_t)j * R + c];
                 if (pair) bi += b * (double)X[(size_t)j * R + c + 1];
