@@ -325,6 +325,7 @@ struct Csr {
     T* ev = nullptr;
     int* cci = nullptr;              // column-major ELL-9 copy (coarse grid levels), or null
     T* cv = nullptr;
+    int cld = 0;                     // its stride (the level's rows)
 };
 
 // Rows of one level: all present chains, continuing chains first.
@@ -860,6 +861,12 @@ struct Engine : bamg_ctx {
             HIPCHK(hipGetLastError());
             return;
         }
+        if (Bm.cci) {
+            hipLaunchKernelGGL((k_sweep_v9<T, T, VW, BS>), dim3(grid), dim3(BS), 0, s, rows, G, FastDiv((uint32_t)G),
+                               Bm.cld, (const int*)Bm.cci, (const T*)Bm.cv, dinv, X, F, Y);
+            HIPCHK(hipGetLastError());
+            return;
+        }
         hipLaunchKernelGGL((k_sweep_v<T, T, VW, BS>), dim3(grid), dim3(BS), 0, s, rows, G, FastDiv((uint32_t)G),
                            (const int*)Bm.rp, (const int*)Bm.ci, (const T*)Bm.v, dinv, X, F, Y);
         HIPCHK(hipGetLastError());
@@ -1000,7 +1007,7 @@ struct Engine : bamg_ctx {
     EllSrc ell_of(int l) const {
         const auto& lv = L[l];
         if (lv.B.eci) return {lv.B.eci, lv.B.ev, 0, EF_ELL4};
-        if (lv.B.cci) return {lv.B.cci, lv.B.cv, lv.rows, EF_ELL9};
+        if (lv.B.cci) return {lv.B.cci, lv.B.cv, lv.B.cld, EF_ELL9};
         return {nullptr, nullptr, 0, EF_CSR};
     }
 
@@ -1064,6 +1071,7 @@ struct Engine : bamg_ctx {
         // flag is read with the other deferred checks at the end of the setup
         LAUNCH((k_csr_to_ell9c<T>), nblk(rows), BAMG_BLK, s, rows, (const int*)lv.B.rp, (const int*)lv.B.ci,
                (const T*)lv.B.v, lv.B.cci, lv.B.cv, derr);
+        lv.B.cld = rows;
     }
 
     void build_level(int l, int use_v, bool inject, bool profile) {

@@ -307,6 +307,46 @@ __global__ void k_csr_to_ell9c(int n, const int* __restrict__ rp, const int* __r
     }
 }
 
+// The multi-vector Jacobi sweep (k_sweep_v) on the column-major ELL-9 copy
+// of a coarse grid level (slot k of row i at k * ld + i): one thread per
+// (row, VW adjacent columns), the row's 9 columns and values read once, the
+// neighbours' columns with vector loads.  Same order of the sums as the CSR
+// kernel (the padding adds exact zeros there and here), so the same bits.
+template <typename T, typename M, int VW, int BS>
+__global__ void __launch_bounds__(BS)
+k_sweep_v9(int n, int G, FastDiv divG, int ld, const int* __restrict__ cci, const M* __restrict__ cv,
+           const M* __restrict__ dinv, const T* __restrict__ X, const T* __restrict__ F, T* __restrict__ Y) {
+    const int t = xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
+    if (t >= n * G) return;
+    const int i = (int)divG.div((uint32_t)t), kg = t - i * G;
+    const int R = G * VW;
+    const size_t base = (size_t)i * R + (size_t)kg * VW;
+    int c[9];
+    M w[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) { c[k] = cci[(size_t)k * ld + i]; w[k] = cv[(size_t)k * ld + i]; }
+    T xt[VW], f[VW], acc[VW];
+    VecIO<T, VW>::ld(X + base, xt);
+    if (F) VecIO<T, VW>::ld(F + base, f);
+    else
+#pragma unroll
+        for (int q = 0; q < VW; ++q) f[q] = (T)0;
+#pragma unroll
+    for (int q = 0; q < VW; ++q) acc[q] = (T)0;
+    const T d = (T)dinv[i];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        T x[VW];
+        VecIO<T, VW>::ld(X + (size_t)c[k] * R + (size_t)kg * VW, x);
+#pragma unroll
+        for (int q = 0; q < VW; ++q) acc[q] += (T)w[k] * x[q];
+    }
+    T y[VW];
+#pragma unroll
+    for (int q = 0; q < VW; ++q) y[q] = xt[q] + d * (f[q] - acc[q]);
+    VecIO<T, VW>::st(Y + base, y);
+}
+
 // sum_k v x over a row of the ELL-9 copy, k = 0..8 (the CSR order; the
 // padding adds exact zeros, as the CSR kernels' padding does).
 template <typename T, typename M>
