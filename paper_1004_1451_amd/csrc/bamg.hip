@@ -1040,14 +1040,20 @@ struct Engine : bamg_ctx {
         for (int which = 0; which < 2; ++which) {
             Csr<T>& M = which == 0 ? f.B : f.Tm;
             Csr<T>& Cm = which == 0 ? c.B : c.Tm;
-            LAUNCH(k_galerkin_symbolic, gb, GAL_THREADS, s, nc, (const ChainGeo*)c.dgeo, c.nch, f.qc, M.rp, M.ci, f.pc,
-                   f.cnt, f.mask);
-            scan(nc, f.cnt, Cm.rp);
-            std::pair<hipEvent_t, hipEvent_t> ev;
-            if (profile) ev = ev_begin();
-            LAUNCH(k_galerkin_numeric<T>, gb, GAL_THREADS, s, nc, (const ChainGeo*)c.dgeo, c.nch, f.qc, (const T*)f.qv,
-                   M.rp, M.ci, (const T*)M.v, f.pc, (const T*)f.pv, f.mask, Cm.rp, Cm.ci, Cm.v);
-            if (profile) ev_end(ev, ev_gal);
+            // B_l's rows from its ELL copy (T_l's from CSR)
+            const EllSrc es = which == 0 ? ell_of(l) : EllSrc{nullptr, nullptr, 0, EF_CSR};
+            ef_dispatch(es.ef, [&](auto efc) {
+                constexpr int EF = decltype(efc)::value;
+                LAUNCH(k_galerkin_symbolic<EF>, gb, GAL_THREADS, s, nc, (const ChainGeo*)c.dgeo, c.nch, f.qc, M.rp,
+                       M.ci, es.c, es.ld, f.pc, f.cnt, f.mask);
+                scan(nc, f.cnt, Cm.rp);
+                std::pair<hipEvent_t, hipEvent_t> ev;
+                if (profile) ev = ev_begin();
+                LAUNCH((k_galerkin_numeric<T, EF>), gb, GAL_THREADS, s, nc, (const ChainGeo*)c.dgeo, c.nch, f.qc,
+                       (const T*)f.qv, M.rp, M.ci, (const T*)M.v, es.c, es.v, es.ld, f.pc, (const T*)f.pv, f.mask,
+                       Cm.rp, Cm.ci, Cm.v);
+                if (profile) ev_end(ev, ev_gal);
+            });
         }
         zero(err, sizeof(int) * 4);
         LAUNCH(k_dinv<T>, nblk(nc), BAMG_BLK, s, nc, c.B.rp, c.B.ci, c.B.v, o.omega, c.dinv, err);

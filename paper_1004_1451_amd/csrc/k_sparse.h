@@ -586,6 +586,29 @@ __device__ __forceinline__ void row_entries(int i, const int* __restrict__ rp, c
     }
 }
 
+// The columns only (for passes that need the pattern): f(column) for the
+// entries row_entries visits, in the same order.
+template <int EF, typename F>
+__device__ __forceinline__ void row_cols(int i, const int* __restrict__ rp, const int* __restrict__ ci,
+                                         const int* __restrict__ eci, int eld, F&& f) {
+    if constexpr (EF == EF_ELL9) {
+        int c[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) c[k] = eci[(size_t)k * eld + i];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) f(c[k]);
+    } else if constexpr (EF == EF_ELL4) {
+        const int4 c4 = *(const int4*)(eci + (size_t)i * 4);
+        f(c4.x);
+        f(c4.y);
+        f(c4.z);
+        f(c4.w);
+    } else {
+        const int p1 = rp[i + 1];
+        for (int p = rp[i]; p < p1; ++p) f(ci[p]);
+    }
+}
+
 // ---------------------------------------------------------------- TV weights
 // Stage 1, per chain (blockIdx.y) and row chunk of seg_rows (blockIdx.x):
 // partial sums of (B x_k)_i^2 and (x_k)_i^2 for the chain's columns k of
@@ -1095,17 +1118,19 @@ __device__ __forceinline__ int box_slot(int I_a, int I_b, int J, const FastDiv& 
 
 // Contribution of Q slot s of coarse row I: the box slots reached through
 // i = qc[9I+s] (mask) and, with vals, tmp[u] = sum_j m_ij p_jJ (M-row order,
-// then P-row order) for J in box slot u.
-template <typename MV, bool VALS>
+// then P-row order) for J in box slot u.  Row i of M comes from the storage
+// EF names (row_entries; mrp null: M = I).  An ELL copy's padding (i, 0)
+// adds zeros and reaches the slots of P row i, which the stored diagonal
+// of M reaches anyway.
+template <typename MV, bool VALS, int EF>
 __device__ __forceinline__ unsigned gal_slot(int coff, int Ia, int Ib, int i, const FastDiv& dcy, int ncx, int ncy,
                                              int periodic, const int* __restrict__ mrp, const int* __restrict__ mci,
-                                             const MV* __restrict__ mv, const int* __restrict__ pc,
+                                             const MV* __restrict__ mv, const int* __restrict__ eci,
+                                             const MV* __restrict__ ev, int eld, const int* __restrict__ pc,
                                              const MV* __restrict__ pv, MV* tmp) {
     unsigned mask = 0;
-    int p0 = mrp ? mrp[i] : 0, p1 = mrp ? mrp[i + 1] : 1;
-    for (int p = p0; p < p1; ++p) {
-        int j = mrp ? mci[p] : i;
-        MV m = (VALS && mrp) ? mv[p] : (MV)1;
+    auto entry = [&](int j, MV mraw) {
+        const MV m = VALS ? mraw : (MV)1;
         int Js[4];
         MV ps[4];
 #pragma unroll
@@ -1124,17 +1149,21 @@ __device__ __forceinline__ unsigned gal_slot(int coff, int Ia, int Ib, int i, co
                 for (int u = 0; u < 9; ++u) tmp[u] += (u == sl) ? c : (MV)0;
             }
         }
-    }
+    };
+    if (!mrp) entry(i, (MV)1);
+    else if constexpr (VALS) row_entries<EF, MV>(i, mrp, mci, mv, eci, ev, eld, entry);
+    else row_cols<EF>(i, mrp, mci, eci, eld, [&](int j) { entry(j, (MV)1); });
     return mask;
 }
 
 // Symbolic pass of Q (M P): 9-bit mask of the coarse box slots reached by row
 // I (every coarse stencil lies in that box: Q, M and P each reach one grid
 // step).  cnt[I] = number of distinct columns.  M == identity when mrp is null.
+template <int EF>
 __global__ void __launch_bounds__(GAL_THREADS)
 k_galerkin_symbolic(int nc, const ChainGeo* __restrict__ geoc, int nch,
                     const int* __restrict__ qc, const int* __restrict__ mrp,
-                    const int* __restrict__ mci, const int* __restrict__ pc,
+                    const int* __restrict__ mci, const int* __restrict__ eci, int eld, const int* __restrict__ pc,
                     int* __restrict__ cnt, unsigned short* __restrict__ mask_out) {
     __shared__ unsigned sm[GAL_THREADS];
     const int lr = threadIdx.x / 9, s = threadIdx.x % 9;
@@ -1146,8 +1175,9 @@ k_galerkin_symbolic(int nc, const ChainGeo* __restrict__ geoc, int nch,
             const ChainGeo g = geoc[find_chain(geoc, nch, I)];
             const int lI = I - g.off;
             int Ia = (int)g.dy.div((uint32_t)lI), Ib = lI - Ia * g.ny;
-            mask = gal_slot<float, false>(g.off, Ia, Ib, i, g.dy, g.nx, g.ny, g.periodic, mrp, mci,
-                                          (const float*)nullptr, pc, (const float*)nullptr, nullptr);
+            mask = gal_slot<float, false, EF>(g.off, Ia, Ib, i, g.dy, g.nx, g.ny, g.periodic, mrp, mci,
+                                              (const float*)nullptr, eci, (const float*)nullptr, eld, pc,
+                                              (const float*)nullptr, nullptr);
         }
     }
     sm[threadIdx.x] = mask;
@@ -1164,11 +1194,12 @@ k_galerkin_symbolic(int nc, const ChainGeo* __restrict__ geoc, int nch,
 // Numeric pass: row I of Q (M P) = sum_s q_Is (sum_j m_ij p_jJ) with the Q
 // slots added in order s = 0..8 (fixed order), written in ascending coarse
 // column at crp[I].
-template <typename MV>
+template <typename MV, int EF>
 __global__ void __launch_bounds__(GAL_THREADS)
 k_galerkin_numeric(int nc, const ChainGeo* __restrict__ geoc, int nch,
                    const int* __restrict__ qc, const MV* __restrict__ qv,
                    const int* __restrict__ mrp, const int* __restrict__ mci, const MV* __restrict__ mv,
+                   const int* __restrict__ eci, const MV* __restrict__ ev, int eld,
                    const int* __restrict__ pc, const MV* __restrict__ pv,
                    const unsigned short* __restrict__ mask_in, const int* __restrict__ crp,
                    int* __restrict__ cci, MV* __restrict__ cv) {
@@ -1187,7 +1218,8 @@ k_galerkin_numeric(int nc, const ChainGeo* __restrict__ geoc, int nch,
         int i = qc[(size_t)I * 9 + s];
         if (i >= 0) {
             MV q = qv[(size_t)I * 9 + s];
-            gal_slot<MV, true>(g.off, Ia, Ib, i, g.dy, ncx, ncy, periodic, mrp, mci, mv, pc, pv, tmp);
+            gal_slot<MV, true, EF>(g.off, Ia, Ib, i, g.dy, ncx, ncy, periodic, mrp, mci, mv, eci, ev, eld, pc, pv,
+                                   tmp);
 #pragma unroll
             for (int u = 0; u < 9; ++u) tmp[u] = q * tmp[u];
         }
