@@ -832,20 +832,18 @@ struct Engine : bamg_ctx {
         if (nnz0 > 4LL * rows) return;
         int* eci = A.alloc<int>((size_t)rows * 4);
         T* ev = A.alloc<T>((size_t)rows * 4);
+        double* ev64 = MIXED ? A.alloc<double>((size_t)rows * 4) : (double*)ev;
         zero(err, sizeof(int) * 4);
-        LAUNCH((k_csr_to_ell4<T>), nblk(rows), BAMG_BLK, s, rows, (const int*)lv.B.rp, (const int*)lv.B.ci,
-               (const T*)lv.B.v, eci, ev, err);
+        if (MIXED)   // one pass over the FP64 rows: the columns, both value copies
+            LAUNCH(k_csr_to_ell4_mixed, nblk(rows), BAMG_BLK, s, rows, (const int*)b0rp, (const int*)b0ci,
+                   (const double*)b0v, eci, (float*)ev, ev64, err);
+        else
+            LAUNCH((k_csr_to_ell4<T>), nblk(rows), BAMG_BLK, s, rows, (const int*)lv.B.rp, (const int*)lv.B.ci,
+                   (const T*)lv.B.v, eci, ev, err);
         if (get1(err)) return;
         lv.B.eci = eci;
         lv.B.ev = ev;
-        if (MIXED) {
-            // same pattern: the column array is rewritten with the same values
-            b0ev = A.alloc<double>((size_t)rows * 4);
-            LAUNCH((k_csr_to_ell4<double>), nblk(rows), BAMG_BLK, s, rows, (const int*)b0rp, (const int*)b0ci,
-                   (const double*)b0v, eci, b0ev, err);
-        } else {
-            b0ev = (double*)ev;
-        }
+        b0ev = ev64;
     }
 
     // -------------------------------------------------------------- setup steps

@@ -307,6 +307,30 @@ __global__ void k_csr_to_ell9c(int n, const int* __restrict__ rp, const int* __r
     }
 }
 
+// Both ELL-4 copies of the finest B in the mixed form from its FP64 CSR in
+// one pass: the shared column array, the FP64 values and their FP32
+// roundings (what the FP32 CSR copy holds); err = 1 when a row has more
+// than 4 entries (the copies are then not used).
+__global__ void k_csr_to_ell4_mixed(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                    const double* __restrict__ v, int* __restrict__ eci, float* __restrict__ ev,
+                                    double* __restrict__ ev64, int* __restrict__ err) {
+    const int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    const int p0 = rp[i], len = rp[i + 1] - p0;
+    if (len > 4) { *err = 1; return; }
+    int c[4];
+    double w[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        c[u] = u < len ? ci[p0 + u] : i;
+        w[u] = u < len ? v[p0 + u] : 0.0;
+    }
+    *(int4*)(eci + (size_t)i * 4) = make_int4(c[0], c[1], c[2], c[3]);
+    *(float4*)(ev + (size_t)i * 4) = make_float4((float)w[0], (float)w[1], (float)w[2], (float)w[3]);
+    ((double2*)(ev64 + (size_t)i * 4))[0] = make_double2(w[0], w[1]);
+    ((double2*)(ev64 + (size_t)i * 4))[1] = make_double2(w[2], w[3]);
+}
+
 // The multi-vector Jacobi sweep (k_sweep_v) on the column-major ELL-9 copy
 // of a coarse grid level (slot k of row i at k * ld + i): one thread per
 // (row, VW adjacent columns), the row's 9 columns and values read once, the
