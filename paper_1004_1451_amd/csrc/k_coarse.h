@@ -759,8 +759,9 @@ k_cz_subst(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const dou
 // finishes its own half of the block rows (side 0 also row m), so the chain
 // of dependent block products is about half that of one sweep over all rows.
 // The banded U_k and L_k take their 3 band terms per row in ascending column
-// order, read from memory one step ahead; every dense product adds over t in
-// ascending order.
+// order, read from memory one step ahead; the dense 64 x 64 by 64 x 16
+// products run on the FP64 matrix cores (cz_mac_mfma), whose operands come
+// from LDS two values per lane per block product.
 __device__ int cz_subst_tw_sequence(int K, int m, int s0, int s1, int side, int* seq) {
     const bool top = s0 <= m - 1, bot = s1 >= m + 1;
     int q = 0;
@@ -778,8 +779,33 @@ __device__ int cz_subst_tw_sequence(int K, int m, int s0, int s1, int side, int*
     return q;
 }
 
+// Row set of a thread in k_cz_subst_tw: wave wv, lane l keeps rows
+// 16 wv + l / 16 + 4 a (a = 0..3) of column l % 16 of the tile, the layout
+// in which v_mfma_f64_16x16x4f64 returns a wave's 16 x 16 product (lane l,
+// register a: row l / 16 + 4 a, column l % 16; its operands: lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16] of the 16 x 4 and 4 x 16 blocks).
+typedef double cz_d4 __attribute__((ext_vector_type(4)));
+
+// acc (+)= sign Ms[rows of this wave, 0:64] * Xs[0:64, column]: 16 products
+// of 16 x 4 by 4 x 16 blocks in ascending k (the zero padding beyond b
+// adds nothing).
+__device__ __forceinline__ void cz_mac_mfma(const double (*Ms)[GJ_NB + 1], const double (*Xs)[CZ_SUB_TC + 1], int wv,
+                                            int lane, double acc[4], double sign) {
+    cz_d4 c = {acc[0], acc[1], acc[2], acc[3]};
+    const int ar = 16 * wv + lane % 16, kq = lane / 16, bc = lane % 16;
+#pragma unroll
+    for (int kk = 0; kk < GJ_NB / 4; ++kk) {
+        const double av = Ms[ar][4 * kk + kq];
+        const double bv = sign * Xs[4 * kk + kq][bc];
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = c[q];
+}
+
 __global__ void __launch_bounds__(BAMG_BLK)
 k_cz_subst_tw(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const double* __restrict__ Fp) {
+    static_assert(BAMG_BLK == 256 && CZ_SUB_TC == 16 && GJ_NB == 64, "four waves of 16 x 16 on a 64 x 16 tile");
     __shared__ double Ms[GJ_NB][GJ_NB + 1];
     __shared__ double Xs[GJ_NB][CZ_SUB_TC + 1];
     __shared__ double Ks[GJ_NB][CZ_SUB_TC + 1];
@@ -795,7 +821,10 @@ k_cz_subst_tw(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const 
     const int w = min(CZ_SUB_TC, n - c0);
     const int s0 = c0 / b, s1 = (c0 + w - 1) / b;
     const bool top = s0 <= m - 1, bot = s1 >= m + 1;
-    const int tid = threadIdx.x, tr = (tid / CZ_SUB_TC) * 4, tc = tid % CZ_SUB_TC;
+    const int tid = threadIdx.x, wv = tid / BAMG_WAVE, lane = tid % BAMG_WAVE, tc = lane % 16;
+    int rows[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rows[q] = 16 * wv + lane / 16 + 4 * q;
     const long long bb = (long long)b * b;
     if (tid == 0) nseq = cz_subst_tw_sequence(K, m, s0, s1, side, seq);
     __syncthreads();
@@ -818,16 +847,22 @@ k_cz_subst_tw(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const 
         if (++sidx < nseq) fetch(sidx);
     };
     fetch(0);
+    auto ident = [&](int blk, double X[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) X[q] = (rows[q] < b && tc < w && blk * b + rows[q] == c0 + tc) ? 1.0 : 0.0;
+    };
+    auto put = [&](const double X[4], double (*Ys)[CZ_SUB_TC + 1]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Ys[rows[q]][tc] = X[q];
+    };
     auto store = [&](int blk, const double X[4]) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int r = tr + a;
-            if (r < b && tc < w) W[(size_t)(blk * b + r) * n + c0 + tc] = X[a];
-        }
+        for (int q = 0; q < 4; ++q)
+            if (rows[q] < b && tc < w) W[(size_t)(blk * b + rows[q]) * n + c0 + tc] = X[q];
     };
     double T[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) T[a] = 0.0;
+    for (int q = 0; q < 4; ++q) T[q] = 0.0;
     // rows of this side's half whose forward part is zero
     if (side == 0)
         for (int s = 0; s < min(s0, m); ++s) store(s, T);
@@ -836,59 +871,59 @@ k_cz_subst_tw(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const 
     // forward from the top: Y_{m-1} ends in Ks
     if (top) {
         for (int s = s0; s <= m - 1; ++s) {
-            cz_ident(s, b, c0, w, tr, tc, T);
+            ident(s, T);
             if (s > s0) {                            // Xs holds Y_{s-1}
                 __syncthreads();
                 next_block();                        // M_s
                 __syncthreads();
-                cz_mac(b, Ms, Xs, tr, tc, T, -1.0);
+                cz_mac_mfma(Ms, Xs, wv, lane, T, -1.0);
             }
             __syncthreads();
-            cz_put(T, Xs, tr, tc);
+            put(T, Xs);
             if (side == 0) store(s, T);
         }
-        cz_put(T, Ks, tr, tc);
+        put(T, Ks);
     }
     // forward from the bottom: V_{m+1} ends in Xs
     if (bot) {
         for (int s = s1; s >= m + 1; --s) {
-            cz_ident(s, b, c0, w, tr, tc, T);
+            ident(s, T);
             if (s < s1) {                            // Xs holds V_{s+1}
                 __syncthreads();
                 next_block();                        // N_s
                 __syncthreads();
-                cz_mac(b, Ms, Xs, tr, tc, T, -1.0);
+                cz_mac_mfma(Ms, Xs, wv, lane, T, -1.0);
             }
             __syncthreads();
-            cz_put(T, Xs, tr, tc);
+            put(T, Xs);
             if (side == 1) store(s, T);
         }
     }
     // middle block row
-    cz_ident(m, b, c0, w, tr, tc, T);
+    ident(m, T);
     if (top) {
         __syncthreads();
         next_block();                                // M_m
         __syncthreads();
-        cz_mac(b, Ms, Ks, tr, tc, T, -1.0);
+        cz_mac_mfma(Ms, Ks, wv, lane, T, -1.0);
     }
     if (bot) {
         __syncthreads();
         next_block();                                // N_m
         __syncthreads();
-        cz_mac(b, Ms, Xs, tr, tc, T, -1.0);
+        cz_mac_mfma(Ms, Xs, wv, lane, T, -1.0);
     }
     __syncthreads();
     next_block();                                    // Z^-1
-    cz_put(T, Xs, tr, tc);
+    put(T, Xs);
     __syncthreads();
     double X[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) X[a] = 0.0;
-    cz_mac(b, Ms, Xs, tr, tc, X, 1.0);
+    for (int q = 0; q < 4; ++q) X[q] = 0.0;
+    cz_mac_mfma(Ms, Xs, wv, lane, X, 1.0);
     if (side == 0) store(m, X);
     __syncthreads();
-    cz_put(X, Xs, tr, tc);                           // X_m
+    put(X, Xs);                                      // X_m
     // this side's half, outwards from row m; U_k (side 0) or L_k (side 1)
     // banded, its 3 band terms per row read one step ahead
     const int slot = side == 0 ? 1 : 2, dk = side == 0 ? -1 : 1;
@@ -896,15 +931,15 @@ k_cz_subst_tw(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const 
     double ub[4][3];
     int tb[4][3];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) cz_band(tr + a, b, d.periodic, tb[a]);
+    for (int q = 0; q < 4; ++q) cz_band(rows[q], b, d.periodic, tb[q]);
     auto load_band = [&](int k) {
         const double* P = F + (long long)(slot * (K + 1) + k) * bb;
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int sl = 0; sl < 3; ++sl) {
-                const int r = tr + a, t = tb[a][sl];
-                ub[a][sl] = (r < b && t >= 0) ? P[r * b + t] : 0.0;
+                const int t = tb[q][sl];
+                ub[q][sl] = (rows[q] < b && t >= 0) ? P[rows[q] * b + t] : 0.0;
             }
     };
     if (cntk > 0) load_band(kfirst);
@@ -912,29 +947,27 @@ k_cz_subst_tw(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const 
         const int k = kfirst + dk * it;
         double U[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int r = tr + a;
-            U[a] = (r < b && tc < w) ? W[(size_t)(k * b + r) * n + c0 + tc] : 0.0;
-        }
+        for (int q = 0; q < 4; ++q)
+            U[q] = (rows[q] < b && tc < w) ? W[(size_t)(k * b + rows[q]) * n + c0 + tc] : 0.0;
         __syncthreads();
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int sl = 0; sl < 3; ++sl) {
-                const int t = tb[a][sl];
-                if (tr + a < b && t >= 0) U[a] = fma(ub[a][sl], -1.0 * Xs[t][tc], U[a]);
+                const int t = tb[q][sl];
+                if (rows[q] < b && t >= 0) U[q] = fma(ub[q][sl], -1.0 * Xs[t][tc], U[q]);
             }
         if (it + 1 < cntk) load_band(k + dk);
         __syncthreads();
         next_block();                                // S_k^-1 or R_k^-1
-        cz_put(U, Xs, tr, tc);
+        put(U, Xs);
         __syncthreads();
 #pragma unroll
-        for (int a = 0; a < 4; ++a) T[a] = 0.0;
-        cz_mac(b, Ms, Xs, tr, tc, T, 1.0);
+        for (int q = 0; q < 4; ++q) T[q] = 0.0;
+        cz_mac_mfma(Ms, Xs, wv, lane, T, 1.0);
         store(k, T);
         __syncthreads();
-        cz_put(T, Xs, tr, tc);
+        put(T, Xs);
     }
 }
 
