@@ -1317,7 +1317,13 @@ struct Engine : bamg_ctx {
             const EllSrc es = ell_of(l);
             long long tot = (long long)rows * VS;
             FastDiv dR((uint32_t)VS);
-            LAUNCH((k_interp<T, T>), nblk(tot), BAMG_BLK, s, rows, VS, dR, lv.pc, (const T*)lv.pv, (const T*)c.V, lv.V);
+            if (VS == 4 || VS == 8 || VS == 12) {
+                auto ik = VS == 4 ? k_interp_rows<T, T, 4> : VS == 8 ? k_interp_rows<T, T, 8> : k_interp_rows<T, T, 12>;
+                LAUNCH(ik, nblk(rows), BAMG_BLK, s, rows, lv.pc, (const T*)lv.pv, (const T*)c.V, lv.V);
+            } else {
+                LAUNCH((k_interp<T, T>), nblk(tot), BAMG_BLK, s, rows, VS, dR, lv.pc, (const T*)lv.pv, (const T*)c.V,
+                       lv.V);
+            }
             T* a = lv.V;
             T* b = sweep_tmp;
             ef_dispatch(es.ef, [&](auto efc) {

@@ -576,6 +576,36 @@ __global__ void k_interp(int n, int R, FastDiv divR, const int* __restrict__ pc,
     Vf[t] = acc;
 }
 
+// The same product with one thread per row and all VP columns (VP a
+// multiple of 4): P's row arrives in one 16-byte load for the columns and
+// one or two for the values, each coarse row and the output row move in
+// 16-byte pieces; the sums run over the slots in the same order.
+template <typename T, typename M, int VP>
+__global__ void k_interp_rows(int n, const int* __restrict__ pc, const M* __restrict__ pv,
+                              const T* __restrict__ Vc, T* __restrict__ Vf) {
+    static_assert(VP % 4 == 0, "row stride must be a multiple of 4");
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    const int4 c4 = *(const int4*)(pc + (size_t)i * 4);
+    M w[4];
+    Ell4Val<M>::ld(pv + (size_t)i * 4, w);
+    const int J[4] = {c4.x, c4.y, c4.z, c4.w};
+    T acc[VP];
+#pragma unroll
+    for (int k = 0; k < VP; ++k) acc[k] = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        if (J[s] < 0) continue;
+        T x[VP];
+#pragma unroll
+        for (int k = 0; k < VP; k += 4) VecIO<T, 4>::ld(Vc + (size_t)J[s] * VP + k, x + k);
+#pragma unroll
+        for (int k = 0; k < VP; ++k) acc[k] += (T)w[s] * x[k];
+    }
+#pragma unroll
+    for (int k = 0; k < VP; k += 4) VecIO<T, 4>::st(Vf + (size_t)i * VP + k, acc + k);
+}
+
 // Calls f(column, value) for the stored entries of row i in CSR order, from
 // the storage EF names: EF_ELL4 the row-major 4-wide copy of the finest
 // level (a row's columns and values move with one 16-byte load each),
