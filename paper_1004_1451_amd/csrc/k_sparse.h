@@ -146,28 +146,33 @@ __global__ void k_scan_block(int n, const int* __restrict__ in, int* __restrict_
     if (threadIdx.x == BAMG_BLK - 1) bsum[blockIdx.x] = sh[threadIdx.x];
 }
 
+// Exclusive scan of the nb block sums in place, total in *total (one
+// block): thread t adds its contiguous chunk of ceil(nb / BAMG_BLK) sums,
+// one block-wide scan of the chunk totals gives each chunk's offset, and the
+// thread writes its chunk's prefixes (integers: the order of the additions
+// does not matter).
 __global__ void k_scan_sums(int nb, int* __restrict__ bsum, int* __restrict__ total) {
     __shared__ int sh[BAMG_BLK];
-    __shared__ int carry;
-    if (threadIdx.x == 0) carry = 0;
+    const int t = threadIdx.x;
+    const int per = (nb + BAMG_BLK - 1) / BAMG_BLK;
+    const int lo = min(nb, t * per), hi = min(nb, lo + per);
+    int own = 0;
+    for (int i = lo; i < hi; ++i) own += bsum[i];
+    sh[t] = own;
     __syncthreads();
-    for (int base = 0; base < nb; base += BAMG_BLK) {
-        int i = base + threadIdx.x;
-        int v = i < nb ? bsum[i] : 0;
-        sh[threadIdx.x] = v;
+    for (int off = 1; off < BAMG_BLK; off <<= 1) {
+        const int v = t >= off ? sh[t - off] : 0;
         __syncthreads();
-        for (int off = 1; off < BAMG_BLK; off <<= 1) {
-            int t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
-            __syncthreads();
-            sh[threadIdx.x] += t;
-            __syncthreads();
-        }
-        if (i < nb) bsum[i] = carry + sh[threadIdx.x] - v;
-        __syncthreads();
-        if (threadIdx.x == BAMG_BLK - 1) carry += sh[threadIdx.x];
+        sh[t] += v;
         __syncthreads();
     }
-    if (threadIdx.x == 0) *total = carry;
+    int run = sh[t] - own;
+    for (int i = lo; i < hi; ++i) {
+        const int v = bsum[i];
+        bsum[i] = run;
+        run += v;
+    }
+    if (t == BAMG_BLK - 1) *total = sh[t];
 }
 
 __global__ void k_scan_add(int n, int* __restrict__ out, const int* __restrict__ bsum, const int* __restrict__ total) {
