@@ -422,7 +422,8 @@ struct Engine : bamg_ctx {
     double *Wp = nullptr, *Fp = nullptr, *ypool = nullptr, *cpool = nullptr, *bcolp = nullptr, *t1 = nullptr,
            *t2 = nullptr, *rre = nullptr, *rim = nullptr, *gtpart = nullptr;
     float* Wfp = nullptr;
-    double *scale = nullptr, *minpiv = nullptr, *cy = nullptr, *csc = nullptr, *dots = nullptr, *vyb = nullptr;
+    double *scale = nullptr, *minpiv = nullptr, *cy = nullptr, *csc = nullptr, *dots = nullptr, *vyb = nullptr,
+           *npart = nullptr;
     double *Vb = nullptr, *Hh = nullptr, *sel_lam = nullptr, *sel_s = nullptr;
     int* nsel = nullptr;
     int HS = 1, SS = 1, DS = 1;
@@ -775,6 +776,7 @@ struct Engine : bamg_ctx {
         nsel = A.alloc<int>((size_t)nch * NS);
         dots = A.alloc<double>((size_t)nch * DS);
         vyb = A.alloc<double>((size_t)nch * DS);
+        npart = A.alloc<double>((size_t)nch * nblk(std::max(1, maxnL)) * 2);
     }
 
     // The coarsest descriptors after the coarsest operators moved (a level
@@ -1238,16 +1240,17 @@ struct Engine : bamg_ctx {
         hipLaunchKernelGGL(k_cz_arn_dots2, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j,
                            (const double*)cpool, (const double*)Vb, dots, DS);
         hipLaunchKernelGGL(k_cz_arn_update2, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, (const double*)ypool,
-                           (const double*)cy, (const double*)dots, (const double*)vyb, DS, Vb, Hh, HS);
+                           (const double*)cy, (const double*)dots, (const double*)vyb, DS, Vb, Hh, HS, npart);
         if (j >= 0) {
             hipLaunchKernelGGL(k_cz_arn_dots, dim3(j + 1, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, 0,
                                (const double*)cpool, (const double*)Vb, dots, DS);
             hipLaunchKernelGGL(k_cz_arn_update, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, 1,
-                               (const double*)ypool, (const double*)cy, (const double*)dots, DS, Vb, Hh, HS);
+                               (const double*)ypool, (const double*)cy, (const double*)dots, DS, Vb, Hh, HS, npart);
         }
         HIPCHK(hipGetLastError());
-        LAUNCH(k_cz_arn_normalize, nch, BAMG_BLK, s, (const CoarseDesc*)cd, j, Vb, Hh, HS, (const double*)ypool, vyb,
-               DS);
+        hipLaunchKernelGGL(k_cz_arn_normalize, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, Vb, Hh, HS, vyb, DS,
+                           (const double*)npart);
+        HIPCHK(hipGetLastError());
     }
 
     // ---- coarsest eigenpairs (Arnoldi, all chains in lockstep) ---------------

@@ -1258,6 +1258,19 @@ __global__ void k_cz_arn_dots(const CoarseDesc* __restrict__ cd, int j, int with
     if (threadIdx.x == 0) dots[(size_t)blockIdx.y * DS + b] = s;
 }
 
+// This block's sums of u^2 and u y (fixed order) into npart[(chain,
+// block) * 2 ..], for k_cz_arn_normalize.
+__device__ __forceinline__ void cz_norm_partials(double ss, double st, double* sh, double* sh2,
+                                                 double* __restrict__ npart) {
+    ss = block_sum(ss, sh);
+    st = block_sum(st, sh2);
+    if (threadIdx.x == 0) {
+        double* o = npart + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 2;
+        o[0] = ss;
+        o[1] = st;
+    }
+}
+
 // The projection against c and the first Gram-Schmidt pass in one pair of
 // launches.  Dots pass (grid (j + 2, chains)): dots[0] = <c, u>, dots[1 + b]
 // = <v_b, u> (b <= j), each by one block in a fixed order.
@@ -1282,8 +1295,9 @@ __global__ void k_cz_arn_dots2(const CoarseDesc* __restrict__ cd, int j, const d
 __global__ void k_cz_arn_update2(const CoarseDesc* __restrict__ cd, int j, const double* __restrict__ y,
                                  const double* __restrict__ cy, const double* __restrict__ dots,
                                  const double* __restrict__ vy, int DS, double* __restrict__ Vb,
-                                 double* __restrict__ H, int HS) {
+                                 double* __restrict__ H, int HS, double* __restrict__ npart) {
     __shared__ double cf[HQR_MAXM];
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE], sh2[BAMG_BLK / BAMG_WAVE];
     const CoarseDesc d = cd[blockIdx.y];
     if (j >= d.am) return;
     const double* dt = dots + (size_t)blockIdx.y * DS;
@@ -1291,25 +1305,31 @@ __global__ void k_cz_arn_update2(const CoarseDesc* __restrict__ cd, int j, const
     for (int b = threadIdx.x; b <= j; b += BAMG_BLK) cf[b] = dt[1 + b] - a * vy[(size_t)blockIdx.y * DS + b];
     __syncthreads();
     double* u = Vb + d.aoff + (size_t)(j + 1) * d.n;
+    double ss = 0, st = 0;
     for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < d.n; i += gridDim.x * BAMG_BLK) {
         double s = u[i];
         s -= y[d.voff + i] * a;
         for (int b = 0; b <= j; ++b) s -= cf[b] * Vb[d.aoff + (size_t)b * d.n + i];
         u[i] = s;
+        ss += s * s;
+        st += s * y[d.voff + i];
     }
     if (blockIdx.x == 0 && (int)threadIdx.x <= j)
         H[(size_t)blockIdx.y * HS + (size_t)j * (d.am + 1) + threadIdx.x] += cf[threadIdx.x];
+    if (j < 0) cz_norm_partials(ss, st, sh, sh2, npart);    // the start vector goes to the norm next
 }
 
 // mode 0: u -= y * dots[0] / cy;  mode 1: u -= sum_{b<=j} dots[b] v_b and
 // H[0..j, j] += dots (H: chain stride HS, column-major ld am+1).
 __global__ void k_cz_arn_update(const CoarseDesc* __restrict__ cd, int j, int mode, const double* __restrict__ y,
                                 const double* __restrict__ cy, const double* __restrict__ dots, int DS,
-                                double* __restrict__ Vb, double* __restrict__ H, int HS) {
+                                double* __restrict__ Vb, double* __restrict__ H, int HS, double* __restrict__ npart) {
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE], sh2[BAMG_BLK / BAMG_WAVE];
     const CoarseDesc d = cd[blockIdx.y];
     if (j >= d.am) return;
     const double* dt = dots + (size_t)blockIdx.y * DS;
     double* u = Vb + d.aoff + (size_t)(j + 1) * d.n;
+    double ss = 0, st = 0;
     for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < d.n; i += gridDim.x * BAMG_BLK) {
         double s = u[i];
         if (mode == 0) {
@@ -1318,37 +1338,35 @@ __global__ void k_cz_arn_update(const CoarseDesc* __restrict__ cd, int j, int mo
             for (int b = 0; b <= j; ++b) s -= dt[b] * Vb[d.aoff + (size_t)b * d.n + i];
         }
         u[i] = s;
+        ss += s * s;
+        st += s * y[d.voff + i];
     }
     if (mode == 1 && blockIdx.x == 0 && (int)threadIdx.x <= j)
         H[(size_t)blockIdx.y * HS + (size_t)j * (d.am + 1) + threadIdx.x] += dt[threadIdx.x];
+    if (npart) cz_norm_partials(ss, st, sh, sh2, npart);
 }
 
 // Normalise basis column j+1 (or column 0 with j = -1): v = u / ||u||,
-// H[j+1, j] = ||u||, and vy[j+1] = <v, y> = <u, y> / ||u|| (summed with the
-// norm) for the projections of later steps.  One block per chain
-// (fixed-order sums).
+// H[j+1, j] = ||u||, and vy[j+1] = <v, y> = <u, y> / ||u|| for the
+// projections of later steps.  The sums come from the partials of the
+// update kernel that formed u (one pair per block, added in block order);
+// grid (blocks, chains) as that kernel's.
 __global__ void k_cz_arn_normalize(const CoarseDesc* __restrict__ cd, int j, double* __restrict__ Vb,
-                                   double* __restrict__ H, int HS, const double* __restrict__ y,
-                                   double* __restrict__ vy, int DS) {
-    __shared__ double sh[BAMG_BLK / BAMG_WAVE], sh2[BAMG_BLK / BAMG_WAVE];
-    __shared__ double nrm;
-    const CoarseDesc d = cd[blockIdx.x];
+                                   double* __restrict__ H, int HS, double* __restrict__ vy, int DS,
+                                   const double* __restrict__ npart) {
+    const CoarseDesc d = cd[blockIdx.y];
     if (j >= d.am || d.am < 1) return;
-    double* u = Vb + d.aoff + (size_t)(j + 1) * d.n;
+    const double* pp = npart + (size_t)blockIdx.y * gridDim.x * 2;
     double s = 0, t = 0;
-    for (int i = threadIdx.x; i < d.n; i += BAMG_BLK) {
-        s += u[i] * u[i];
-        t += u[i] * y[d.voff + i];
+    for (int q = 0; q < (int)gridDim.x; ++q) { s += pp[2 * q]; t += pp[2 * q + 1]; }
+    const double nrm = sqrt(s);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (j >= 0) H[(size_t)blockIdx.y * HS + (size_t)j * (d.am + 1) + j + 1] = nrm;
+        vy[(size_t)blockIdx.y * DS + j + 1] = nrm > 0 ? t / nrm : 0.0;
     }
-    s = block_sum(s, sh);
-    t = block_sum(t, sh2);
-    if (threadIdx.x == 0) {
-        nrm = sqrt(s);
-        if (j >= 0) H[(size_t)blockIdx.x * HS + (size_t)j * (d.am + 1) + j + 1] = nrm;
-        vy[(size_t)blockIdx.x * DS + j + 1] = nrm > 0 ? t / nrm : 0.0;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < d.n; i += BAMG_BLK) u[i] = nrm > 0 ? u[i] / nrm : 0.0;
+    double* u = Vb + d.aoff + (size_t)(j + 1) * d.n;
+    for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < d.n; i += gridDim.x * BAMG_BLK)
+        u[i] = nrm > 0 ? u[i] / nrm : 0.0;
 }
 
 // Ritz vector of entry e of chain (blockIdx.y): v = Vb[:, 0:am] s_e.
