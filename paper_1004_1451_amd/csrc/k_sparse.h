@@ -1068,12 +1068,19 @@ k_ls_fit(int n, const ChainGeo* __restrict__ geo, int nch, int Ru, int use_v, co
          int caliber, int* __restrict__ pc, MP* __restrict__ pv, T* __restrict__ inject,
          unsigned char* __restrict__ jcnt, const int* __restrict__ brp, const int* __restrict__ bci,
          const M* __restrict__ bv, float* __restrict__ feat_out, float* __restrict__ slotw_out) {
-    int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
-    if (i >= n) return;
-    const int ch = find_chain(geo, nch, i);
+    const int t = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (t >= n) return;
+    const int ch = find_chain(geo, nch, t);
     const ChainGeo g = geo[ch];
-    const int li = i - g.off;
-    const int ia = (int)g.dy.div((uint32_t)li), ib = li - ia * g.ny;
+    // Thread t takes a point of its own grid row: on rows with C points
+    // (even ia) the odd columns (F points) come first and the even ones (C
+    // points) after them, so a wavefront's lanes mostly take the same branch.
+    const int lt = t - g.off;
+    const int ia = (int)g.dy.div((uint32_t)lt), kk = lt - ia * g.ny;
+    const int nf = g.ny / 2;
+    const int ib = (ia & 1) ? kk : (kk < nf ? 2 * kk + 1 : 2 * (kk - nf));
+    const int li = ia * g.ny + ib;
+    const int i = g.off + li;
     if (((ia | ib) & 1) == 0) {
         int I = g.coff + (ia >> 1) * g.ncy + (ib >> 1);
         pc[(size_t)i * 4] = I; pv[(size_t)i * 4] = (MP)1;
