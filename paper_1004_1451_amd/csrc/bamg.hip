@@ -1242,10 +1242,10 @@ struct Engine : bamg_ctx {
         hipLaunchKernelGGL(k_cz_arn_update2, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, (const double*)ypool,
                            (const double*)cy, (const double*)dots, (const double*)vyb, DS, Vb, Hh, HS, npart);
         if (j >= 0) {
-            hipLaunchKernelGGL(k_cz_arn_dots, dim3(j + 1, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, 0,
-                               (const double*)cpool, (const double*)Vb, dots, DS);
-            hipLaunchKernelGGL(k_cz_arn_update, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, 1,
-                               (const double*)ypool, (const double*)cy, (const double*)dots, DS, Vb, Hh, HS, npart);
+            hipLaunchKernelGGL(k_cz_arn_dots, dim3(j + 1, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j,
+                               (const double*)Vb, dots, DS);
+            hipLaunchKernelGGL(k_cz_arn_update, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, (const double*)ypool,
+                               (const double*)dots, DS, Vb, Hh, HS, npart);
         }
         HIPCHK(hipGetLastError());
         hipLaunchKernelGGL(k_cz_arn_normalize, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, Vb, Hh, HS, vyb, DS,

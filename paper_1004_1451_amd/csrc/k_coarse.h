@@ -1242,16 +1242,16 @@ k_cz_arn_gemv(const CoarseDesc* __restrict__ cd, int j, const double* __restrict
     }
 }
 
-// dots[chain*DS + b] = <x_b, u> for basis columns b <= nb (x_0 = c when
-// with_c: then only one dot, <c, u>).  One block per (b, chain).
-__global__ void k_cz_arn_dots(const CoarseDesc* __restrict__ cd, int j, int with_c, const double* __restrict__ cvec,
-                              const double* __restrict__ Vb, double* __restrict__ dots, int DS) {
+// Second Gram-Schmidt pass: dots[chain*DS + b] = <v_b, u> for basis columns
+// b <= j.  One block per (b, chain).
+__global__ void k_cz_arn_dots(const CoarseDesc* __restrict__ cd, int j, const double* __restrict__ Vb,
+                              double* __restrict__ dots, int DS) {
     __shared__ double sh[BAMG_BLK / BAMG_WAVE];
     const CoarseDesc d = cd[blockIdx.y];
     const int b = blockIdx.x;
-    if (j >= d.am || (with_c ? b > 0 : b > j)) return;
+    if (j >= d.am || b > j) return;
     const double* u = Vb + d.aoff + (size_t)(j + 1) * d.n;
-    const double* x = with_c ? cvec + d.voff : Vb + d.aoff + (size_t)b * d.n;
+    const double* x = Vb + d.aoff + (size_t)b * d.n;
     double s = 0;
     for (int i = threadIdx.x; i < d.n; i += BAMG_BLK) s += x[i] * u[i];
     s = block_sum(s, sh);
@@ -1319,11 +1319,11 @@ __global__ void k_cz_arn_update2(const CoarseDesc* __restrict__ cd, int j, const
     if (j < 0) cz_norm_partials(ss, st, sh, sh2, npart);    // the start vector goes to the norm next
 }
 
-// mode 0: u -= y * dots[0] / cy;  mode 1: u -= sum_{b<=j} dots[b] v_b and
-// H[0..j, j] += dots (H: chain stride HS, column-major ld am+1).
-__global__ void k_cz_arn_update(const CoarseDesc* __restrict__ cd, int j, int mode, const double* __restrict__ y,
-                                const double* __restrict__ cy, const double* __restrict__ dots, int DS,
-                                double* __restrict__ Vb, double* __restrict__ H, int HS, double* __restrict__ npart) {
+// Second Gram-Schmidt pass: u -= sum_{b<=j} dots[b] v_b and H[0..j, j] +=
+// dots (H: chain stride HS, column-major ld am+1); npart as k_cz_arn_update2.
+__global__ void k_cz_arn_update(const CoarseDesc* __restrict__ cd, int j, const double* __restrict__ y,
+                                const double* __restrict__ dots, int DS, double* __restrict__ Vb,
+                                double* __restrict__ H, int HS, double* __restrict__ npart) {
     __shared__ double sh[BAMG_BLK / BAMG_WAVE], sh2[BAMG_BLK / BAMG_WAVE];
     const CoarseDesc d = cd[blockIdx.y];
     if (j >= d.am) return;
@@ -1332,18 +1332,14 @@ __global__ void k_cz_arn_update(const CoarseDesc* __restrict__ cd, int j, int mo
     double ss = 0, st = 0;
     for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < d.n; i += gridDim.x * BAMG_BLK) {
         double s = u[i];
-        if (mode == 0) {
-            s -= y[d.voff + i] * (dt[0] / cy[blockIdx.y]);
-        } else {
-            for (int b = 0; b <= j; ++b) s -= dt[b] * Vb[d.aoff + (size_t)b * d.n + i];
-        }
+        for (int b = 0; b <= j; ++b) s -= dt[b] * Vb[d.aoff + (size_t)b * d.n + i];
         u[i] = s;
         ss += s * s;
         st += s * y[d.voff + i];
     }
-    if (mode == 1 && blockIdx.x == 0 && (int)threadIdx.x <= j)
+    if (blockIdx.x == 0 && (int)threadIdx.x <= j)
         H[(size_t)blockIdx.y * HS + (size_t)j * (d.am + 1) + threadIdx.x] += dt[threadIdx.x];
-    if (npart) cz_norm_partials(ss, st, sh, sh2, npart);
+    cz_norm_partials(ss, st, sh, sh2, npart);
 }
 
 // Normalise basis column j+1 (or column 0 with j = -1): v = u / ||u||,
