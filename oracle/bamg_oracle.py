@@ -85,7 +85,27 @@ def _with_pattern(M: sp.csr_matrix, pat: sp.csr_matrix) -> sp.csr_matrix:
 # ---------------------------------------------------------------------------
 # Grids and full coarsening (Section 3; Section 5: every other grid point in
 # both directions).  State s = a*ny + b.
+#
+# Along one grid direction of length m the coarse coordinates are the even
+# positions, and on a side that is not periodic also the last position m-1:
+# the experiments of Section 5 use sides 2^k + 1, where "every other point"
+# keeps both ends of the side coarse, and this keeps both ends coarse on
+# sides of any length.  A coarse coordinate y has rank (y + 1) // 2 among the
+# coarse coordinates of its side, so a non-periodic side of m points leaves
+# m // 2 + 1 of them and a periodic side (m even) m / 2.
 # ---------------------------------------------------------------------------
+def coarse_coords(m: int, periodic: bool) -> np.ndarray:
+    """The coarse positions 0 <= y < m of one grid direction, ascending."""
+    c = np.arange(m) % 2 == 0
+    if not periodic and m > 0:
+        c[m - 1] = True
+    return np.nonzero(c)[0]
+
+
+def coarse_side(m: int, periodic: bool) -> int:
+    return len(coarse_coords(m, periodic))
+
+
 @dataclass(frozen=True)
 class Grid:
     nx: int
@@ -97,15 +117,15 @@ class Grid:
         return self.nx * self.ny
 
     def coarse(self) -> "Grid":
-        return Grid((self.nx + 1) // 2, (self.ny + 1) // 2, self.periodic)
+        return Grid(coarse_side(self.nx, self.periodic), coarse_side(self.ny, self.periodic), self.periodic)
 
     def can_coarsen(self) -> bool:
         """Full coarsening keeps every coarse stencil within the 3x3 box only
-        for even periodic sides with coarse side >= 3; non-periodic sides need
-        at least two points."""
+        for even periodic sides with coarse side >= 3; a non-periodic grid
+        must get smaller (a side of 1 or 2 points keeps every point)."""
         if self.periodic:
             return all(m % 2 == 0 and m // 2 >= 3 for m in (self.nx, self.ny))
-        return self.nx * self.ny > 1
+        return self.coarse().n < self.n
 
 
 def level_plan(grid: Grid, levels: int, coarse_max: int = 1024) -> list[Grid]:
@@ -127,41 +147,64 @@ def level_plan(grid: Grid, levels: int, coarse_max: int = 1024) -> list[Grid]:
 
 
 def c_points(g: Grid) -> np.ndarray:
-    """Fine indices of the coarse points (a even and b even), in coarse order."""
-    a, b = np.meshgrid(np.arange(0, g.nx, 2), np.arange(0, g.ny, 2), indexing="ij")
+    """Fine indices of the coarse points (both coordinates coarse), in coarse
+    order (row-major over the coarse coordinates)."""
+    ca = coarse_coords(g.nx, g.periodic)
+    cb = coarse_coords(g.ny, g.periodic)
+    a, b = np.meshgrid(ca, cb, indexing="ij")
     return (a * g.ny + b).ravel()
 
 
+def _dir_table(m: int, periodic: bool):
+    """Per position y of a direction of length m: whether it is coarse, its
+    rank among the coarse positions (-1 if fine), and the positions of the
+    coarse neighbours that interpolate to it: y itself at a coarse position
+    (one), y - 1 and y + 1 elsewhere (two; both exist since an F position is
+    odd and the last position of a non-periodic side is coarse; periodic
+    sides wrap)."""
+    cc = coarse_coords(m, periodic)
+    isc = np.zeros(m, dtype=bool); isc[cc] = True
+    rank = np.full(m, -1, dtype=np.int64); rank[cc] = np.arange(len(cc))
+    y = np.arange(m)
+    lo = np.where(isc, y, (y - 1) % m)
+    hi = np.where(isc, y, (y + 1) % m)
+    return isc, rank, lo, hi, np.where(isc, 1, 2)
+
+
 def neighbour_slots(g: Grid) -> np.ndarray:
-    """Coarse neighbourhood N_i of every point (eq. neighbor_def, read as the
-    coarse points within Chebyshev distance 1 on the grid, wrapping when
-    periodic).  Returns an (n, 4) int array of coarse indices, -1 where a slot
-    is empty, slots in lexicographic order of the offset (da, db)."""
+    """Coarse neighbourhood N_i of every point (eq. neighbor_def).  Reading:
+    the coarse points (a', b') with a' among the coarse neighbours of a in
+    its direction and b' among those of b (``_dir_table``), leaving out the
+    point itself.  When the coarse positions are exactly the even ones this
+    is the set of coarse points within Chebyshev distance 1; next to the last
+    coarse position of a non-periodic even side it leaves out the coarse
+    point across a coarse row or column, so that Q, B and P each reach one
+    coarse step and every coarse operator keeps the 3x3 box stencil.
+    Returns an (n, 4) int array of coarse indices, -1 where a slot is empty,
+    slots in lexicographic order of the offset (da, db)."""
     cg = g.coarse()
-    a = np.arange(g.n) // g.ny
-    b = np.arange(g.n) % g.ny
+    isa, ra, loa, hia, na_ = _dir_table(g.nx, g.periodic)
+    isb, rb, lob, hib, nb_ = _dir_table(g.ny, g.periodic)
+    s = np.arange(g.n)
+    a, b = s // g.ny, s % g.ny
+    fine = ~(isa[a] & isb[b])
     slots = np.full((g.n, 4), -1, dtype=np.int64)
-    cnt = np.zeros(g.n, dtype=np.int64)
-    for da in (-1, 0, 1):
-        for db in (-1, 0, 1):
-            if da == 0 and db == 0:
-                continue
-            na, nb = a + da, b + db
-            if g.periodic:
-                na %= g.nx; nb %= g.ny
-                ok = np.ones(g.n, dtype=bool)
-            else:
-                ok = (na >= 0) & (na < g.nx) & (nb >= 0) & (nb < g.ny)
-            ok &= (na % 2 == 0) & (nb % 2 == 0)
+    for ka in (0, 1):
+        for kb in (0, 1):
+            ok = fine & (ka < na_[a]) & (kb < nb_[b])
             idx = np.nonzero(ok)[0]
-            slots[idx, cnt[idx]] = (na[idx] // 2) * cg.ny + nb[idx] // 2
-            cnt[idx] += 1
+            pa = (loa if ka == 0 else hia)[a[idx]]
+            pb = (lob if kb == 0 else hib)[b[idx]]
+            slots[idx, ka * nb_[b[idx]] + kb] = ra[pa] * cg.ny + rb[pb]
     return slots
 
 
 def is_c_point(g: Grid) -> np.ndarray:
+    isa = np.zeros(g.nx, dtype=bool); isa[coarse_coords(g.nx, g.periodic)] = True
+    isb = np.zeros(g.ny, dtype=bool); isb[coarse_coords(g.ny, g.periodic)] = True
     s = np.arange(g.n)
-    return ((s // g.ny) % 2 == 0) & ((s % g.ny) % 2 == 0)
+    return isa[s // g.ny] & isb[s % g.ny]
+
 
 
 @dataclass

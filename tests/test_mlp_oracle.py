@@ -120,15 +120,18 @@ def test_features_are_scale_free():
 
 
 def test_one_slot_feature_is_the_least_squares_weight():
-    ch, Bl, g, U, w = _level0(N=31)          # side 32: points on the last column have one slot
+    ch, Bl, g, U, w = _level0(N=31)
     F, G, b, sigma, valid, isC = M.level_features(U, w, Bl, g)
+    # caliber 1: every F point interpolates from the one slot Algorithm 2
+    # picks, with the one-point least-squares weight b_s / G_ss
+    P1, J1, _ = O.ls_fit(U, w, g, 1)
+    W1 = M.slot_weights(P1, g)
+    idx = np.nonzero(~isC)[0]
+    assert np.all(J1[idx].sum(1) == 1)
+    s = np.argmax(J1[idx], axis=1)
+    assert np.allclose(F[idx, 12 + s], W1[idx, s], rtol=1e-12, atol=0)
     P, J, slots = O.ls_fit(U, w, g, 4)
     Ws = M.slot_weights(P, g)
-    one = (~isC) & (valid.sum(1) == 1)
-    assert one.sum() > 0
-    s = np.argmax(valid[one], axis=1)
-    idx = np.nonzero(one)[0]
-    assert np.allclose(F[idx, 12 + s], Ws[idx, s], rtol=1e-12, atol=0)
     # the functional at the fitted weights is the fit's minimum, below the
     # value at any one-slot weight
     i = np.nonzero((~isC) & (valid.sum(1) == 4))[0][0]

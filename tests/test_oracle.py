@@ -52,8 +52,60 @@ def test_lattice_closed_form_is_stationary():
 
 
 # --------------------------------------------------------------- grids
+def test_coarse_positions_keep_both_ends():
+    # Section 5 runs on sides 2^k + 1, where every other point keeps both ends
+    # coarse; the reading keeps both ends coarse on every non-periodic side.
+    for m in range(1, 40):
+        want = sorted(set(range(0, m, 2)) | {m - 1})
+        assert list(O.coarse_coords(m, False)) == want
+        assert O.coarse_side(m, False) == m // 2 + 1
+    for k in range(1, 8):
+        m = 2 ** k + 1
+        assert list(O.coarse_coords(m, False)) == list(range(0, m, 2))
+    for m in (6, 8, 64, 1024):
+        assert list(O.coarse_coords(m, True)) == list(range(0, m, 2))
+    g = O.Grid(6, 9, False)
+    isC = O.is_c_point(g).reshape(6, 9)
+    assert [a for a in range(6) if isC[a, 0]] == [0, 2, 4, 5]
+    assert [b for b in range(9) if isC[0, b]] == [0, 2, 4, 6, 8]
+    # coarse index = rank of the coarse point in row-major order
+    cp = O.c_points(g)
+    assert np.all(np.diff(cp) > 0) and len(cp) == g.coarse().n == 4 * 5
+    assert np.array_equal(np.nonzero(O.is_c_point(g))[0], cp)
+
+
+def _slots_brute(g):
+    """N_i by enumeration: coarse points within Chebyshev distance 1 of i
+    that do not leave a direction in which i itself sits on a coarse line."""
+    ca = set(O.coarse_coords(g.nx, g.periodic).tolist())
+    cb = set(O.coarse_coords(g.ny, g.periodic).tolist())
+    rank_a = {a: k for k, a in enumerate(sorted(ca))}
+    rank_b = {b: k for k, b in enumerate(sorted(cb))}
+    out = []
+    for s in range(g.n):
+        a, b = divmod(s, g.ny)
+        want = []
+        if not (a in ca and b in cb):
+            for da, db in itertools.product((-1, 0, 1), repeat=2):
+                if (da, db) == (0, 0):
+                    continue
+                if (a in ca and da != 0) or (b in cb and db != 0):
+                    continue
+                na, nb = a + da, b + db
+                if g.periodic:
+                    na %= g.nx; nb %= g.ny
+                elif not (0 <= na < g.nx and 0 <= nb < g.ny):
+                    continue
+                if na in ca and nb in cb:
+                    want.append(rank_a[na] * g.coarse().ny + rank_b[nb])
+        out.append(want)
+    return out
+
+
 def test_neighbour_slots_brute_force():
-    for g in (O.Grid(7, 6, False), O.Grid(8, 6, True)):
+    # grids whose coarse positions are the even ones: N_i is every coarse
+    # point within Chebyshev distance 1 (the reading as first stated)
+    for g in (O.Grid(7, 9, False), O.Grid(8, 6, True), O.Grid(5, 5, False)):
         slots = O.neighbour_slots(g)
         cg = g.coarse()
         for s in range(g.n):
@@ -67,18 +119,99 @@ def test_neighbour_slots_brute_force():
                     na %= g.nx; nb %= g.ny
                 elif not (0 <= na < g.nx and 0 <= nb < g.ny):
                     continue
-                if na % 2 == 0 and nb % 2 == 0:
+                if na % 2 == 0 and nb % 2 == 0 and not (a % 2 == 0 and b % 2 == 0):
                     want.append((na // 2) * cg.ny + nb // 2)
             got = [int(v) for v in slots[s] if v >= 0]
             assert got == want
+    # even non-periodic sides (last position coarse too)
+    for g in (O.Grid(8, 6, False), O.Grid(6, 9, False), O.Grid(4, 4, False), O.Grid(8, 6, True)):
+        slots = O.neighbour_slots(g)
+        for s, want in enumerate(_slots_brute(g)):
+            assert [int(v) for v in slots[s] if v >= 0] == want
+    # every F point has 2 or 4 slots, C points none
+    g = O.Grid(10, 7, False)
+    cnt = (O.neighbour_slots(g) >= 0).sum(1)
+    isC = O.is_c_point(g)
+    assert np.all(cnt[isC] == 0) and set(cnt[~isC].tolist()) <= {2, 4}
+
+
+def _box_coarse_operator(g, slots, seed=0):
+    """Q B P for a random 9-point B on grid g and a P with positive weights on
+    the given slots (C points: unit rows); returns (Bc, Q, P, coarse grid)."""
+    rng = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    for s in range(g.n):
+        a, b = divmod(s, g.ny)
+        for da, db in itertools.product((-1, 0, 1), repeat=2):
+            na, nb = a + da, b + db
+            if g.periodic:
+                na %= g.nx; nb %= g.ny
+            elif not (0 <= na < g.nx and 0 <= nb < g.ny):
+                continue
+            rows.append(s); cols.append(na * g.ny + nb)
+            vals.append(4.0 if (da, db) == (0, 0) else -rng.random())
+    B = sp.csr_matrix((vals, (rows, cols)), shape=(g.n, g.n))
+    isC = O.is_c_point(g)
+    cidx = np.cumsum(isC) - 1
+    pr, pc, pv = [], [], []
+    for s in range(g.n):
+        if isC[s]:
+            pr.append(s); pc.append(cidx[s]); pv.append(1.0)
+            continue
+        for J in slots[s]:
+            if J >= 0:
+                pr.append(s); pc.append(J); pv.append(0.1 + rng.random())
+    P = sp.csr_matrix((pv, (pr, pc)), shape=(g.n, int(isC.sum())))
+    Q = O.averaging_q(P)
+    return O.galerkin(Q, B, P), Q, P, g.coarse()
+
+
+def _in_box(M, cg):
+    r, c = M.nonzero()
+    da = np.abs(r // cg.ny - c // cg.ny)
+    db = np.abs(r % cg.ny - c % cg.ny)
+    if cg.periodic:
+        da = np.minimum(da, cg.nx - da); db = np.minimum(db, cg.ny - db)
+    return bool(np.all(da <= 1) and np.all(db <= 1))
+
+
+def test_even_side_coarse_operators_keep_the_box():
+    # Q, B and P each reach one grid step, so Q B P has a 3x3 coarse stencil
+    # (every coarse operator of Sections 4-5 stays a 9-point operator)
+    for g in (O.Grid(8, 6, False), O.Grid(6, 9, False), O.Grid(10, 10, False), O.Grid(9, 9, False),
+              O.Grid(8, 8, True)):
+        Bc, Q, P, cg = _box_coarse_operator(g, O.neighbour_slots(g))
+        assert _in_box(Bc, cg)
+        assert np.abs(np.asarray(Q.sum(0)).ravel() - 1).max() < 1e-15      # 1^T Q = 1^T
+    # the plain Chebyshev-1 set next to the doubled coarse line would couple
+    # coarse points two steps apart: the reason for the reading
+    g = O.Grid(8, 8, False)
+    ca = set(O.coarse_coords(8, False).tolist())
+    rank = {a: k for k, a in enumerate(sorted(ca))}
+    cheb = np.full((g.n, 4), -1)
+    for s in range(g.n):
+        a, b = divmod(s, g.ny)
+        if a in ca and b in ca:
+            continue
+        k = 0
+        for da, db in itertools.product((-1, 0, 1), repeat=2):
+            na, nb = a + da, b + db
+            if (da, db) != (0, 0) and 0 <= na < 8 and 0 <= nb < 8 and na in ca and nb in ca and k < 4:
+                cheb[s, k] = rank[na] * 5 + rank[nb]; k += 1
+    Bc, _, _, cg = _box_coarse_operator(g, cheb)
+    assert not _in_box(Bc, cg)
 
 
 def test_level_plan_configs():
     assert [g.n for g in O.level_plan(O.Grid(33, 33, False), 3)] == [1089, 289, 81]
     assert [g.nx for g in O.level_plan(O.Grid(1024, 1024, True), 5)] == [1024, 512, 256, 128, 64]
-    assert [g.nx for g in O.level_plan(O.Grid(2048, 2048, False), 6)] == [2048, 1024, 512, 256, 128, 64]
+    assert [g.nx for g in O.level_plan(O.Grid(2048, 2048, False), 6)] == [2048, 1025, 513, 257, 129, 65]
+    assert [g.nx for g in O.level_plan(O.Grid(129, 129, False), 6)] == [129, 65, 33, 17, 9, 5]
     with pytest.raises(ValueError):
         O.level_plan(O.Grid(10, 10, True), 3)     # 10 -> 5 is odd and periodic
+    with pytest.raises(ValueError):
+        O.level_plan(O.Grid(2, 2, False), 2)      # a side of two keeps both points
+    assert not O.Grid(2, 2, False).can_coarsen() and O.Grid(3, 2, False).can_coarsen()
 
 
 # --------------------------------------------------------------- relaxation
@@ -247,7 +380,8 @@ def test_inject():
     g = O.Grid(5, 4, False)
     X = np.arange(20 * 3, dtype=float).reshape(20, 3)
     Xc = O.inject(X, g)
-    want = np.array([X[a * 4 + b] for a in (0, 2, 4) for b in (0, 2)])
+    # side 4 keeps positions 0, 2 and 3 (both ends), side 5 keeps 0, 2, 4
+    want = np.array([X[a * 4 + b] for a in (0, 2, 4) for b in (0, 2, 3)])
     assert np.array_equal(Xc, want)
 
 
@@ -378,3 +512,18 @@ def test_stationary_uniform_network_closed_form():
     x, info, h = O.stationary(ch.to_scipy(), _grid(ch), 6, O.Options(levels=3), tol=1e-13)
     assert info.converged
     assert np.abs(x - ch.exact).sum() < 1e-11
+
+
+@pytest.mark.parametrize("N", [127, 511])
+def test_cycle_counts_stay_flat_on_even_sides(N):
+    # Section 5, Tables 1-2: the number of cycles stays roughly constant as
+    # the grid grows; an even side (N + 1) must not cost more than the odd
+    # side next to it by more than two cycles, and six levels on side 1024
+    # reach 1e-10 within ten cycles
+    counts = []
+    for M in (N, N + 1):
+        ch = C.tandem_queue(M)
+        _, info, h = O.stationary(ch.to_scipy(), _grid(ch), 12, O.Options(levels=6), tol=1e-10)
+        assert info.converged
+        counts.append(info.cycles)
+    assert counts[0] <= counts[1] + 2 and counts[0] <= 10, counts

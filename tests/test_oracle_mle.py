@@ -70,3 +70,13 @@ def test_mle_iteration_closed_form():
     x, info, _ = O.mle_iteration(ch.to_scipy(), _grid(ch), 8, O.Options(levels=3, mu=2), tol=1e-11, max_cycles=40)
     assert info.converged
     assert np.abs(x - ch.exact).sum() < 1e-9
+
+
+@pytest.mark.parametrize("N", [127, 255])
+def test_mle_iteration_converges_on_even_sided_six_level_tandems(N):
+    # Section 4.1 / Table 2: the MLE iteration converges in a roughly constant
+    # number of cycles as the grid grows; on sides 128 and 256 (even, not
+    # periodic) with six levels it must reach the paper's 1e-8
+    ch = C.tandem_queue(N)
+    x, info, _ = O.mle_iteration(ch.to_scipy(), _grid(ch), 12, O.Options(levels=6), tol=1e-8, max_cycles=25)
+    assert info.converged and info.cycles <= 20, (info.cycles, info.history)
