@@ -128,10 +128,10 @@ constexpr int GT_RCH = 128;       // row chunk of the y^T W partials
 struct GridH {
     int nx, ny, periodic;
     long long n() const { return (long long)nx * ny; }
-    GridH coarse() const { return {(nx + 1) / 2, (ny + 1) / 2, periodic}; }
+    GridH coarse() const { return {grid_coarse_side(nx, periodic), grid_coarse_side(ny, periodic), periodic}; }
     bool can_coarsen() const {
         if (periodic) return nx % 2 == 0 && ny % 2 == 0 && nx / 2 >= 3 && ny / 2 >= 3;
-        return n() > 1;
+        return coarse().n() < n();   // a side of one or two points keeps them all
     }
 };
 
@@ -417,6 +417,13 @@ struct Engine : bamg_ctx {
     // coarsest levels (one per chain)
     std::vector<CoarseDesc> cdh;
     CoarseDesc* cd = nullptr;
+    // Descriptors the block path runs on: cdh, except that the coarsest grid
+    // of a single chain with rows of GJ_NB + 1 points (bordered) is replaced
+    // by its main part (k_bd_* in k_coarse.h).
+    std::vector<CoarseDesc> cdsh;
+    CoarseDesc* cds = nullptr;
+    bool bordered = false;
+    double *bdZ = nullptr, *bdY = nullptr, *bdG = nullptr, *bdH = nullptr, *bdS = nullptr;
     int NVt = 0;                     // sum of coarsest sizes
     int AMmax = 0, maxnL = 0, nxmax = 0;
     double *Wp = nullptr, *Fp = nullptr, *ypool = nullptr, *cpool = nullptr, *bcolp = nullptr, *t1 = nullptr,
@@ -721,6 +728,7 @@ struct Engine : bamg_ctx {
         int voff = 0;
         AMmax = 0; maxnL = 0; nxmax = 0;
         dense_fallback = false;
+        bordered = false;
         cdh.clear();
         for (int c = 0; c < nch; ++c) {
             const auto& ch = chains[c];
@@ -733,11 +741,17 @@ struct Engine : bamg_ctx {
                 dense_fallback = true;
             } else {
                 d.n = (int)gh.n(); d.nx = gh.nx; d.ny = gh.ny; d.periodic = gh.periodic; d.dy = FastDiv((uint32_t)gh.ny);
-                if (gh.ny > GJ_NB || gh.nx > CZ_MAX_NX) dense_fallback = true;
+                if (gh.ny > GJ_NB || gh.nx > CZ_MAX_NX) {
+                    if (nch == 1 && !gh.periodic && gh.ny == GJ_NB + 1 && gh.nx <= GJ_NB + 1) bordered = true;
+                    else dense_fallback = true;
+                }
             }
             d.row0 = L[lc].geo[c].off;
             d.voff = voff;
             d.woff = woff;
+            d.soff = woff;
+            d.sld = d.n;
+            d.bord = 0;
             d.boff = boff;
             d.aoff = aoff;
             d.am = (o.n_eig > 1) ? std::max(0, std::min({o.arnoldi_m, d.n - 1, HQR_MAXM})) : 0;
@@ -756,7 +770,22 @@ struct Engine : bamg_ctx {
             fail(BAMG_EUNSUPPORTED, "batched chains need coarsest grids with ny <= %d and nx <= %d", GJ_NB, CZ_MAX_NX);
         NVt = voff;
         cd = A.upload(cdh);
-        Wp = A.alloc<double>(woff);
+        cdsh = cdh;
+        long long wall = woff;
+        if (bordered) {
+            CoarseDesc& m = cdsh[0];
+            m.ny = GJ_NB;
+            m.n = m.nx * GJ_NB;
+            m.dy = FastDiv((uint32_t)GJ_NB);
+            m.woff = woff;              // A^-1 of the main part, after the chain's W
+            m.bord = 1;
+            wall += (long long)m.n * m.n;
+            const size_t zs = (size_t)m.n * GJ_NB;
+            for (double** p : {&bdZ, &bdY, &bdG, &bdH}) *p = A.alloc<double>(zs);
+            bdS = A.alloc<double>((size_t)GJ_NB * GJ_NB);
+        }
+        cds = A.upload(cdsh);
+        Wp = A.alloc<double>(wall);
         if (MIXED) Wfp = A.alloc<float>(woff);
         Fp = A.alloc<double>(std::max<long long>(boff, 1));
         for (double** p : {&ypool, &cpool, &bcolp, &t1, &t2, &rre, &rim}) *p = A.alloc<double>(NVt);
@@ -788,8 +817,12 @@ struct Engine : bamg_ctx {
             auto& d = cdh[c];
             d.brp = L[lc].B.rp; d.bci = L[lc].B.ci; d.bv = L[lc].B.v;
             d.trp = L[lc].Tm.rp; d.tci = L[lc].Tm.ci; d.tv = L[lc].Tm.v;
+            auto& m = cdsh[c];
+            m.brp = d.brp; m.bci = d.bci; m.bv = d.bv;
+            m.trp = d.trp; m.tci = d.tci; m.tv = d.tv;
         }
         HIPCHK(hipMemcpyAsync(cd, cdh.data(), sizeof(CoarseDesc) * cdh.size(), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(cds, cdsh.data(), sizeof(CoarseDesc) * cdsh.size(), hipMemcpyHostToDevice, s));
         sync();
     }
 
@@ -1137,43 +1170,44 @@ struct Engine : bamg_ctx {
             dense_gj_inverse();
         } else {
             int bbmax = 0;
-            for (auto& d : cdh) bbmax = std::max(bbmax, d.ny * d.ny);
-            hipLaunchKernelGGL(k_cz_extract, dim3(nblk(bbmax), nxmax, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd,
+            for (auto& d : cdsh) bbmax = std::max(bbmax, d.ny * d.ny);
+            hipLaunchKernelGGL(k_cz_extract, dim3(nblk(bbmax), nxmax, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cds,
                                (const double*)Wp, Fp);
             HIPCHK(hipGetLastError());
             bool arrow = false, plain = false;
-            for (auto& d : cdh) {
+            for (auto& d : cdsh) {
                 if (d.n < 2) continue;
                 if (d.periodic && d.nx >= 3) arrow = true; else plain = true;
             }
             // chains without the arrow: the twisted factorisation, top and
             // bottom halves at once, then the middle block row
             if (plain) {
-                hipLaunchKernelGGL(k_cz_lu_half, dim3(2, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, Fp,
+                hipLaunchKernelGGL(k_cz_lu_half, dim3(2, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cds, Fp,
                                    (const double*)scale, minpiv + nch);
-                hipLaunchKernelGGL(k_cz_lu_mid, dim3(nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, Fp,
+                hipLaunchKernelGGL(k_cz_lu_mid, dim3(nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cds, Fp,
                                    (const double*)scale, (const double*)(minpiv + nch), minpiv);
             }
             if (arrow) {
                 const dim3 gl(4, nch);
                 for (int k = 0; k + 1 < nxmax; ++k) {
-                    hipLaunchKernelGGL(k_cz_lu_step, gl, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, k, Fp,
+                    hipLaunchKernelGGL(k_cz_lu_step, gl, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cds, k, Fp,
                                        (const double*)scale, minpiv);
-                    hipLaunchKernelGGL(k_cz_elim_arrow, dim3(2, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, k,
+                    hipLaunchKernelGGL(k_cz_elim_arrow, dim3(2, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cds, k,
                                        Fp);
                     HIPCHK(hipGetLastError());
                 }
-                hipLaunchKernelGGL(k_cz_lu_step, gl, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, -1, Fp,
+                hipLaunchKernelGGL(k_cz_lu_step, gl, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cds, -1, Fp,
                                    (const double*)scale, minpiv);
             }
             HIPCHK(hipGetLastError());
             if (arrow)
                 hipLaunchKernelGGL(k_cz_subst, dim3(ceil_div(maxnL, CZ_SUB_TC), nch), dim3(BAMG_BLK), 0, s,
-                                   (const CoarseDesc*)cd, Wp, (const double*)Fp);
+                                   (const CoarseDesc*)cds, Wp, (const double*)Fp);
             if (plain)
                 hipLaunchKernelGGL(k_cz_subst_tw, dim3(ceil_div(maxnL, CZ_SUB_TC), 2, nch), dim3(BAMG_BLK), 0, s,
-                                   (const CoarseDesc*)cd, Wp, (const double*)Fp);
+                                   (const CoarseDesc*)cds, Wp, (const double*)Fp);
             HIPCHK(hipGetLastError());
+            if (bordered) bordered_inverse();
         }
         hipLaunchKernelGGL(k_cz_zero_border, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, Wp);
         // y = [-Binv b_col; 1]
@@ -1207,6 +1241,28 @@ struct Engine : bamg_ctx {
         st.coarsest_min_pivot = mn;
         if (!(mn > 1e-12)) fail(BAMG_ESINGULAR, "coarsest pivot %.3e below 1e-12 of max |B_L|", mn);
         if (MIXED) LAUNCH((k_cast<double, float>), nblk(wtot), BAMG_BLK, s, wtot, (const double*)Wp, Wfp);
+    }
+
+    // The coarsest inverse of a bordered grid from the main part's inverse
+    // (k_bd_* in k_coarse.h): Z, Y, the Schur complement S and its inverse,
+    // G, H, then W in natural order.
+    void bordered_inverse() {
+        const CoarseDesc& m = cdsh[0];
+        const int ne = cdh[0].nx - 1;
+        const long long zs = (long long)m.n * GJ_NB;
+        const int gz = (int)std::min<long long>(ceil_div(zs, BAMG_BLK), 4096);
+        LAUNCH(k_bd_zy, gz, BAMG_BLK, s, (const CoarseDesc*)cd, (const CoarseDesc*)cds, (const double*)Wp, bdZ, bdY);
+        LAUNCH(k_bd_schur, 1, BAMG_BLK, s, (const CoarseDesc*)cd, (const double*)Wp, (const double*)bdZ, bdS);
+        LAUNCH(k_gj_diag, 1, CZ_GJ_THREADS, s, GJ_NB, 0, ne, bdS, (const double*)scale, minpiv);
+        LAUNCH(k_bd_gh, gz, BAMG_BLK, s, (const CoarseDesc*)cd, (const CoarseDesc*)cds, (const double*)bdS,
+               (const double*)bdZ, (const double*)bdY, bdG, bdH);
+        hipLaunchKernelGGL(k_bd_combine_main, dim3(m.nx, m.nx), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd,
+                           (const CoarseDesc*)cds, Wp, (const double*)bdG, (const double*)bdY);
+        HIPCHK(hipGetLastError());
+        const long long te = (long long)cdh[0].nx * cdh[0].n;
+        LAUNCH(k_bd_combine_edge, (int)std::min<long long>(ceil_div(te, BAMG_BLK), 4096), BAMG_BLK, s,
+               (const CoarseDesc*)cd, (const CoarseDesc*)cds, Wp, (const double*)bdG, (const double*)bdH,
+               (const double*)bdS);
     }
 
     // Dense blocked Gauss-Jordan (coarse sides > 64; single chain only).

@@ -118,6 +118,29 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
 
 __host__ __device__ __forceinline__ int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+// Full coarsening along one grid direction of length m: the coarse
+// positions are the even ones and, on a side that is not periodic, also the
+// last position m - 1 (both ends of every side stay coarse, as "every other
+// point" does on the sides 2^k + 1 of Section 5).  A coarse position y has
+// rank (y + 1) >> 1 among the coarse positions of its side; coarse position
+// A sits at fine position 2A, or m - 1 for the last one of a non-periodic
+// side.  A fine position is odd and interpolates from y - 1 and y + 1, both
+// coarse (periodic sides wrap).
+__host__ __device__ __forceinline__ bool grid_cpos(int y, int m, int periodic) {
+    return !(y & 1) || (!periodic && y == m - 1);
+}
+__host__ __device__ __forceinline__ int grid_coarse_side(int m, int periodic) {
+    return periodic ? (m + 1) / 2 : m / 2 + 1;
+}
+__host__ __device__ __forceinline__ int grid_fine_pos(int A, int m, int periodic) {
+    return (periodic || 2 * A < m) ? 2 * A : m - 1;
+}
+// Number of fine positions (odd ones, the last of a non-periodic side
+// excepted) along a side of length m.
+__host__ __device__ __forceinline__ int grid_fine_count(int m, int periodic) {
+    return m / 2 - ((!periodic && m > 1 && !(m & 1)) ? 1 : 0);
+}
+
 // Several chains are handled as one block-diagonal system: on every level the
 // rows of chain c form the range [off, off + n).  Chains are ordered by depth
 // (deepest first), so the chains that continue to the next level always form

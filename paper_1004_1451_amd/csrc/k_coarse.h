@@ -21,6 +21,9 @@
 
 struct CoarseDesc {
     int n, nx, ny, periodic;
+    long long soff;           // dense B_L the block extraction reads (W pool offset)
+    int sld;                  // its row length
+    int bord;                 // 1: the main part of a bordered grid (below)
     int row0;                 // first row of the chain on its coarsest level
     int voff;                 // offset of its length-n vectors in the vector pools
     long long woff;           // offset of its n x n block in the W pool
@@ -98,7 +101,7 @@ __global__ void k_cz_extract(const CoarseDesc* __restrict__ cd, const double* __
     const int nx = d.nx, b = d.ny, K = nx - 1, n = d.n, bb = b * b;
     if (k >= nx) return;
     const bool arrow = d.periodic && nx >= 3;
-    const double* A = Wp + d.woff;
+    const double* A = Wp + d.soff;
     for (int kind = 0; kind < 5; ++kind) {
         int bi, bj;
         if (kind == 0) { bi = k; bj = k; }
@@ -110,8 +113,11 @@ __global__ void k_cz_extract(const CoarseDesc* __restrict__ cd, const double* __
         for (int e = blockIdx.x * BAMG_BLK + threadIdx.x; e < bb; e += gridDim.x * BAMG_BLK) {
             int r = e / b, c = e % b;
             int gi = bi * b + r, gj = bj * b + c;
-            double v = A[(size_t)gi * n + gj];
-            if (gi == n - 1 || gj == n - 1) v = (gi == gj) ? 1.0 : 0.0;
+            // the main part of a bordered grid: grid rows of b + 1 points in
+            // the source, no padded unknown
+            const int si = d.bord ? bi * (b + 1) + r : gi, sj = d.bord ? bj * (b + 1) + c : gj;
+            double v = A[(size_t)si * d.sld + sj];
+            if (!d.bord && (gi == n - 1 || gj == n - 1)) v = (gi == gj) ? 1.0 : 0.0;
             dst[e] = v;
         }
     }
@@ -968,6 +974,189 @@ k_cz_subst_tw(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const 
         store(k, T);
         __syncthreads();
         put(T, Xs);
+    }
+}
+
+// ---------------------------------------------------------------- bordered grids
+// A coarsest grid (not periodic) whose rows hold GJ_NB + 1 points, with at
+// most GJ_NB + 1 rows, is split into its first GJ_NB columns (the main part:
+// block tridiagonal with GJ_NB x GJ_NB blocks, inverted by the block path
+// above into Am) and its last column (the border: nx - 1 points; the last
+// point of the grid is the padded unknown).  With the padded operator
+// K = [[A, E], [F, D]] (main part first, then the border), Z = A^-1 E,
+// Y = F A^-1, the Schur complement S = D - F Z and G = Z S^-1, H = S^-1 Y:
+//   K^-1 = [[A^-1 + G Y, -G], [-H, S^-1]].
+// S is a nonsingular M-matrix as K is (no pivoting).  In the 3x3 box a
+// border point (e, GJ_NB) couples with the main part only through column
+// GJ_NB - 1 of grid rows e - 1 .. e + 1, so a column of Z and a row of Y are
+// sums of at most three columns / rows of A^-1 (in ascending grid row).
+// Z is nm x GJ_NB and G likewise (row-major, columns e >= ne zero); Y and H
+// are GJ_NB x nm (rows e >= ne zero); S is GJ_NB x GJ_NB.  One chain.
+#define BD_B GJ_NB
+
+__device__ __forceinline__ int bd_nat_main(int i) { return (i / BD_B) * (BD_B + 1) + i % BD_B; }
+__device__ __forceinline__ int bd_nat_edge(int e) { return e * (BD_B + 1) + BD_B; }
+
+__global__ void __launch_bounds__(BAMG_BLK)
+k_bd_zy(const CoarseDesc* __restrict__ cd, const CoarseDesc* __restrict__ cs, const double* __restrict__ Wp,
+        double* __restrict__ Z, double* __restrict__ Y) {
+    const CoarseDesc d = cd[0], m = cs[0];
+    const int nx = d.nx, ne = nx - 1, nm = m.n, n = d.n;
+    const double* Bd = Wp + d.woff;
+    const double* Am = Wp + m.woff;
+    const long long tot = (long long)nm * BD_B;
+    for (long long t = (long long)blockIdx.x * BAMG_BLK + threadIdx.x; t < tot; t += (long long)gridDim.x * BAMG_BLK) {
+        // Z[i, e] (e fastest) and Y[e, j] (j fastest) share the index t
+        {
+            const int i = (int)(t / BD_B), e = (int)(t % BD_B);
+            double z = 0.0;
+            if (e < ne) {
+                const int ce = bd_nat_edge(e);
+                for (int a = max(e - 1, 0); a <= min(e + 1, nx - 1); ++a) {
+                    const int cm = a * BD_B + BD_B - 1;
+                    z += Am[(size_t)i * nm + cm] * Bd[(size_t)bd_nat_main(cm) * n + ce];
+                }
+            }
+            Z[t] = z;
+        }
+        {
+            const int e = (int)(t / nm), j = (int)(t % nm);
+            double y = 0.0;
+            if (e < ne) {
+                const int re = bd_nat_edge(e);
+                for (int a = max(e - 1, 0); a <= min(e + 1, nx - 1); ++a) {
+                    const int rm = a * BD_B + BD_B - 1;
+                    y += Bd[(size_t)re * n + bd_nat_main(rm)] * Am[(size_t)rm * nm + j];
+                }
+            }
+            Y[t] = y;
+        }
+    }
+}
+
+// S = D - F Z on the ne x ne border block (ld GJ_NB); the entries outside are
+// left alone (the Gauss-Jordan step pads with the identity).
+__global__ void __launch_bounds__(BAMG_BLK)
+k_bd_schur(const CoarseDesc* __restrict__ cd, const double* __restrict__ Wp, const double* __restrict__ Z,
+           double* __restrict__ S) {
+    const CoarseDesc d = cd[0];
+    const int nx = d.nx, ne = nx - 1, n = d.n;
+    const double* Bd = Wp + d.woff;
+    for (int t = threadIdx.x; t < BD_B * BD_B; t += BAMG_BLK) {
+        const int e = t / BD_B, e2 = t % BD_B;
+        if (e >= ne || e2 >= ne) continue;
+        const int re = bd_nat_edge(e);
+        double v = Bd[(size_t)re * n + bd_nat_edge(e2)];
+        for (int a = max(e - 1, 0); a <= min(e + 1, nx - 1); ++a) {
+            const int rm = a * BD_B + BD_B - 1;
+            v -= Bd[(size_t)re * n + bd_nat_main(rm)] * Z[(size_t)rm * BD_B + e2];
+        }
+        S[t] = v;
+    }
+}
+
+// G = Z S^-1 and H = S^-1 Y (S^-1 in LDS; sums over e ascending).
+__global__ void __launch_bounds__(BAMG_BLK)
+k_bd_gh(const CoarseDesc* __restrict__ cd, const CoarseDesc* __restrict__ cs, const double* __restrict__ Si,
+        const double* __restrict__ Z, const double* __restrict__ Y, double* __restrict__ G, double* __restrict__ H) {
+    __shared__ double sS[BD_B][BD_B + 1];
+    const int ne = cd[0].nx - 1, nm = cs[0].n;
+    for (int t = threadIdx.x; t < BD_B * BD_B; t += BAMG_BLK) {
+        const int e = t / BD_B, e2 = t % BD_B;
+        sS[e][e2] = (e < ne && e2 < ne) ? Si[t] : 0.0;
+    }
+    __syncthreads();
+    const long long tot = (long long)nm * BD_B;
+    for (long long t = (long long)blockIdx.x * BAMG_BLK + threadIdx.x; t < tot; t += (long long)gridDim.x * BAMG_BLK) {
+        {
+            const int i = (int)(t / BD_B), e2 = (int)(t % BD_B);
+            double g = 0.0;
+            for (int e = 0; e < ne; ++e) g += Z[(size_t)i * BD_B + e] * sS[e][e2];
+            G[t] = g;
+        }
+        {
+            const int e = (int)(t / nm), j = (int)(t % nm);
+            double h = 0.0;
+            for (int e2 = 0; e2 < ne; ++e2) h += sS[e][e2] * Y[(size_t)e2 * nm + j];
+            H[t] = h;
+        }
+    }
+}
+
+// W (natural order) from the pieces: grid (nx, nx) workgroups for the main x
+// main tiles (grid rows a, a2): W = A^-1 + G Y, the rank-ne product summed
+// over e ascending in chunks of 16 staged through LDS; thread (ty, tx) takes
+// rows ty + 16 p and columns tx + 16 q.
+#define BD_KC 16
+__global__ void __launch_bounds__(BAMG_BLK)
+k_bd_combine_main(const CoarseDesc* __restrict__ cd, const CoarseDesc* __restrict__ cs, double* __restrict__ Wp,
+                  const double* __restrict__ G, const double* __restrict__ Y) {
+    static_assert(BAMG_BLK == 256 && BD_B == 64, "16 x 16 threads on a 64 x 64 tile");
+    __shared__ double Gs[BD_B][BD_KC + 1];
+    __shared__ double Ys[BD_KC][BD_B + 1];
+    const CoarseDesc d = cd[0], m = cs[0];
+    const int ne = d.nx - 1, nm = m.n, n = d.n;
+    const double* Am = Wp + m.woff;
+    double* W = Wp + d.woff;
+    const int a = blockIdx.y, a2 = blockIdx.x;
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int i0 = a * BD_B, j0 = a2 * BD_B;
+    double acc[4][4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = Am[(size_t)(i0 + ty + 16 * p) * nm + j0 + tx + 16 * q];
+    for (int e0 = 0; e0 < ne; e0 += BD_KC) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < BD_B * BD_KC; t += BAMG_BLK) {
+            const int r = t / BD_KC, k = t % BD_KC;
+            Gs[r][k] = (e0 + k < ne) ? G[(size_t)(i0 + r) * BD_B + e0 + k] : 0.0;
+            const int k2 = t / BD_B, c = t % BD_B;
+            Ys[k2][c] = (e0 + k2 < ne) ? Y[(size_t)(e0 + k2) * nm + j0 + c] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < BD_KC; ++k) {
+            double gv[4], yv[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) gv[p] = Gs[ty + 16 * p][k];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) yv[q] = Ys[k][tx + 16 * q];
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[p][q] = fma(gv[p], yv[q], acc[p][q]);
+        }
+    }
+    const int r0 = a * (BD_B + 1), c0 = a2 * (BD_B + 1);
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) W[(size_t)(r0 + ty + 16 * p) * n + c0 + tx + 16 * q] = acc[p][q];
+}
+
+// The border rows and columns of W: row of border point e: -H (main
+// columns), S^-1 (border columns); column of border point e: -G (main rows);
+// the padded unknown's row and column are zero.
+__global__ void __launch_bounds__(BAMG_BLK)
+k_bd_combine_edge(const CoarseDesc* __restrict__ cd, const CoarseDesc* __restrict__ cs, double* __restrict__ Wp,
+                  const double* __restrict__ G, const double* __restrict__ H, const double* __restrict__ Si) {
+    const CoarseDesc d = cd[0];
+    const int nx = d.nx, ne = nx - 1, nm = cs[0].n, n = d.n;
+    double* W = Wp + d.woff;
+    const long long tot = (long long)nx * n;
+    for (long long t = (long long)blockIdx.x * BAMG_BLK + threadIdx.x; t < tot; t += (long long)gridDim.x * BAMG_BLK) {
+        const int e = (int)(t / n), j = (int)(t % n);
+        const int ja = j / (BD_B + 1), jc = j % (BD_B + 1);
+        // row of border point e, column j
+        double v = 0.0;
+        if (e < ne) {
+            if (jc < BD_B) v = -H[(size_t)e * nm + ja * BD_B + jc];
+            else if (ja < ne) v = Si[e * BD_B + ja];
+        }
+        W[(size_t)bd_nat_edge(e) * n + j] = v;
+        // column of border point e, row j (main rows only: border rows above)
+        if (jc < BD_B) W[(size_t)j * n + bd_nat_edge(e)] = e < ne ? -G[(size_t)(ja * BD_B + jc) * BD_B + e] : 0.0;
     }
 }
 

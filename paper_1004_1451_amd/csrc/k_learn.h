@@ -44,8 +44,8 @@ k_ls_fit_learn(int n, const ChainGeo* __restrict__ geo, int nch, int Ru, const T
             const ChainGeo g = geo[ch];
             const int li = i - g.off;
             const int ia = (int)g.dy.div((uint32_t)li), ib = li - ia * g.ny;
-            if (((ia | ib) & 1) == 0) {
-                const int I = g.coff + (ia >> 1) * g.ncy + (ib >> 1);
+            if (grid_cpos(ia, g.nx, g.periodic) && grid_cpos(ib, g.ny, g.periodic)) {
+                const int I = g.coff + ((ia + 1) >> 1) * g.ncy + ((ib + 1) >> 1);
                 pc[(size_t)i * 4] = I; pv[(size_t)i * 4] = (MP)1;
 #pragma unroll
                 for (int s = 1; s < 4; ++s) { pc[(size_t)i * 4 + s] = -1; pv[(size_t)i * 4 + s] = (MP)0; }

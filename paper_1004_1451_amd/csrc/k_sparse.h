@@ -530,7 +530,7 @@ __global__ void k_restrict_box(int nc, const ChainGeo* __restrict__ geoc, const 
 #pragma unroll
     for (int s = 0; s < 9; ++s) {
         if (!((m >> s) & 1)) continue;
-        int na = 2 * A + s / 3 - 1, nb = 2 * Bq + s % 3 - 1;
+        int na = grid_fine_pos(A, gf.nx, gf.periodic) + s / 3 - 1, nb = grid_fine_pos(Bq, gf.ny, gf.periodic) + s % 3 - 1;
         if (gf.periodic) {
             na = na < 0 ? na + gf.nx : (na >= gf.nx ? na - gf.nx : na);
             nb = nb < 0 ? nb + gf.ny : (nb >= gf.ny ? nb - gf.ny : nb);
@@ -829,11 +829,16 @@ __device__ __forceinline__ void ls_point(int i, const ChainGeo& g, int ia, int i
     int ns = 0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) { P.sf[s] = i; P.sc[s] = -1; }
+    // per direction: a coarse position takes offset 0 only, a fine one -1
+    // and +1 (both coarse); the slots are the product, lexicographic in
+    // (da, db), without (0, 0)
+    const bool ca = grid_cpos(ia, g.nx, g.periodic), cb = grid_cpos(ib, g.ny, g.periodic);
 #pragma unroll
     for (int da = -1; da <= 1; ++da)
 #pragma unroll
         for (int db = -1; db <= 1; ++db) {
             if (da == 0 && db == 0) continue;
+            if ((da == 0) != ca || (db == 0) != cb) continue;
             int na = ia + da, nb = ib + db;
             if (g.periodic) {
                 na = na < 0 ? na + g.nx : (na >= g.nx ? na - g.nx : na);
@@ -841,11 +846,13 @@ __device__ __forceinline__ void ls_point(int i, const ChainGeo& g, int ia, int i
             } else if (na < 0 || na >= g.nx || nb < 0 || nb >= g.ny) {
                 continue;
             }
-            if (((na | nb) & 1) != 0) continue;
-            // at most 4 coarse points in the box; ns < 4 always holds here
+            // at most 4 coarse points; ns < 4 always holds here
 #pragma unroll
             for (int s = 0; s < 4; ++s)
-                if (s == ns) { P.sf[s] = g.off + na * g.ny + nb; P.sc[s] = g.coff + (na >> 1) * ncy + (nb >> 1); }
+                if (s == ns) {
+                    P.sf[s] = g.off + na * g.ny + nb;
+                    P.sc[s] = g.coff + ((na + 1) >> 1) * ncy + ((nb + 1) >> 1);
+                }
             ++ns;
         }
     const int valid = (1 << ns) - 1;
@@ -1077,12 +1084,13 @@ k_ls_fit(int n, const ChainGeo* __restrict__ geo, int nch, int Ru, int use_v, co
     // points) after them, so a wavefront's lanes mostly take the same branch.
     const int lt = t - g.off;
     const int ia = (int)g.dy.div((uint32_t)lt), kk = lt - ia * g.ny;
-    const int nf = g.ny / 2;
-    const int ib = (ia & 1) ? kk : (kk < nf ? 2 * kk + 1 : 2 * (kk - nf));
+    const bool rowc = grid_cpos(ia, g.nx, g.periodic);
+    const int nf = grid_fine_count(g.ny, g.periodic);
+    const int ib = !rowc ? kk : (kk < nf ? 2 * kk + 1 : grid_fine_pos(kk - nf, g.ny, g.periodic));
     const int li = ia * g.ny + ib;
     const int i = g.off + li;
-    if (((ia | ib) & 1) == 0) {
-        int I = g.coff + (ia >> 1) * g.ncy + (ib >> 1);
+    if (rowc && grid_cpos(ib, g.ny, g.periodic)) {
+        int I = g.coff + ((ia + 1) >> 1) * g.ncy + ((ib + 1) >> 1);
         pc[(size_t)i * 4] = I; pv[(size_t)i * 4] = (MP)1;
 #pragma unroll
         for (int s = 1; s < 4; ++s) { pc[(size_t)i * 4 + s] = -1; pv[(size_t)i * 4 + s] = (MP)0; }
@@ -1124,7 +1132,7 @@ __global__ void k_build_q(int nc, const ChainGeo* __restrict__ geoc, const Chain
     const ChainGeo g = geof[ch];
     const int lI = I - gc.off;
     int A = (int)gc.dy.div((uint32_t)lI), Bq = lI - A * gc.ny;
-    int fa = 2 * A, fb = 2 * Bq;
+    int fa = grid_fine_pos(A, g.nx, g.periodic), fb = grid_fine_pos(Bq, g.ny, g.periodic);
     int fi[9];
     double fv[9];
 #pragma unroll

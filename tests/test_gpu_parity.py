@@ -74,6 +74,11 @@ CASES = [
     ("tandem40_ragged", lambda: C.tandem_queue(40), 12, 3),
     ("lattice48p", lambda: C.weighted_lattice(48, seed=3), 12, 3),
     ("uniform21", lambda: C.weighted_lattice(21, periodic=False, uniform_weights=True), 6, 3),
+    # even non-periodic sides: the last row and column stay coarse
+    ("tandem39_even", lambda: C.tandem_queue(39), 12, 3),
+    ("tandem63_even", lambda: C.tandem_queue(63), 12, 4),
+    ("uniform20_even", lambda: C.weighted_lattice(20, periodic=False, uniform_weights=True), 6, 3),
+    ("lattice14x9_mixed", lambda: C.weighted_lattice(14, seed=4, periodic=False, my=9), 8, 3),
 ]
 
 
@@ -175,7 +180,13 @@ SMALL_COARSEST = [
     ("tandem4_2x2", lambda: C.tandem_queue(4), 3),
     ("tandem8_5x5", lambda: C.tandem_queue(8), 2),
     ("lattice7x13_4x7", lambda: C.weighted_lattice(7, seed=1, periodic=False, my=13), 2),
-    ("lattice2x20_1x10", lambda: C.weighted_lattice(2, seed=2, periodic=False, my=20), 2),
+    ("lattice2x20_2x11", lambda: C.weighted_lattice(2, seed=2, periodic=False, my=20), 2),
+    # rows of 65 points: the main part (64 columns) by the block path and the
+    # last column as a border (Schur complement)
+    ("lattice9x129_5x65", lambda: C.weighted_lattice(9, seed=5, periodic=False, my=129), 2),
+    ("lattice2x129_2x65", lambda: C.weighted_lattice(2, seed=6, periodic=False, my=129), 2),
+    ("lattice1x65_1x65", lambda: C.weighted_lattice(1, seed=7, periodic=False, my=65), 1),
+    ("tandem127_65x65", lambda: C.tandem_queue(127), 2),
 ]
 
 
