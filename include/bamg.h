@@ -381,6 +381,17 @@ int bamg_mlp_init(uint64_t seed, float* params, void* stream);
 /* out[i] = network(feat[i]) for n points (device arrays). */
 int bamg_mlp_forward(const float* feat, int64_t n, const float* params, float* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same
+   inference as bamg_mlp_forward, bit for bit, staged through a static device
+   array of the library (8.02 MiB per GPU, held until the process ends)
+   instead of allocated buffers.  n <= 131072 points (larger n returns
+   BAMG_EINVAL); feat (n x 24), params and out (n x 4) are the caller's device
+   arrays, stream a stream of the current device.  Calls on one GPU share the
+   array: calls that overlap on one GPU (other streams, other threads) race.
+   Calls no allocating routine.  Synchronises the stream. */
+int bamg_mlp_forward_noalloc(const float* feat, int64_t n, const float* params, float* out, void* stream);
+
 /* Masked mean squared error over all n points (one batch) and its gradient
    (device, BAMG_MLP_NPARAM floats); *loss on the host. */
 int bamg_mlp_loss_grad(const float* feat, const float* tgt, int64_t n, const float* params, float* grad,

@@ -35,7 +35,7 @@ ERROR_NAMES = {EINVAL: "EINVAL", ENOTSTOCH: "ENOTSTOCH", EZERODIAG: "EZERODIAG",
 EXPORTS = ["bamg_options_default", "bamg_setup", "bamg_solve", "bamg_free", "bamg_last_error", "bamg_get_stats",
            "bamg_level_info_get", "bamg_export", "bamg_apply_vcycle", "bamg_relax", "bamg_setup_batched",
            "bamg_solve_batched", "bamg_trim", "bamg_mlp_init", "bamg_mlp_forward", "bamg_mlp_loss_grad",
-           "bamg_mlp_train", "bamg_mle_iterate"]
+           "bamg_mlp_train", "bamg_mle_iterate", "bamg_mlp_forward_noalloc"]
 
 
 class BamgError(RuntimeError):
@@ -141,6 +141,8 @@ def load():
     lib.bamg_mlp_init.restype = C.c_int
     lib.bamg_mlp_forward.argtypes = [vp, i64, vp, vp, vp]
     lib.bamg_mlp_forward.restype = C.c_int
+    lib.bamg_mlp_forward_noalloc.argtypes = [vp, i64, vp, vp, vp]
+    lib.bamg_mlp_forward_noalloc.restype = C.c_int
     lib.bamg_mlp_loss_grad.argtypes = [vp, vp, i64, vp, vp, C.POINTER(C.c_double), vp]
     lib.bamg_mlp_loss_grad.restype = C.c_int
     lib.bamg_mlp_train.argtypes = [vp, vp, i64, vp, vp, i64, vp, C.POINTER(MlpTrainOpts), C.POINTER(MlpTrainInfo), vp]
@@ -325,6 +327,14 @@ def mlp_forward(feat, params, stream=None):
     out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
     _check(load().bamg_mlp_forward(C.c_void_p(feat.data_ptr()), n, C.c_void_p(params.data_ptr()),
                                    C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+def mlp_forward_noalloc(feat, params, out, stream=None):
+    """The allocation-free inference call: out (n x 4, FP32, device) is the
+    caller's; the library stages through its static scratch."""
+    _check(load().bamg_mlp_forward_noalloc(C.c_void_p(feat.data_ptr()), feat.shape[0], C.c_void_p(params.data_ptr()),
+                                           C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out
 
 

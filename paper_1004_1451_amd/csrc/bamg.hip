@@ -2532,6 +2532,37 @@ int setup_common(int32_t nchains, const int64_t* off, const int32_t* row_ptr, co
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI
+// ------------------------------------------------------------------ scratch
+// The allocation-free inference entry point keeps its staging in one
+// file-scope device array per GPU: the packed network (MlpPack, padded to 256
+// bytes), then the inputs as bfloat16 rows of MLP_INP values for at most
+// NOALLOC_MLP_MAXN points (8.02 MiB in all).  Host code never uses the
+// array's name as an address: its device address comes from
+// hipGetSymbolAddress, once per device with that device current.
+constexpr long long NOALLOC_MLP_MAXN = 1LL << 17;
+constexpr size_t NOALLOC_PK_BYTES = (sizeof(MlpPack) + 255) / 256 * 256;
+constexpr size_t NOALLOC_BYTES = NOALLOC_PK_BYTES + (size_t)NOALLOC_MLP_MAXN * MLP_INP * sizeof(unsigned short);
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEV = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEV] = {};
+
+// Device address of the current device's scratch (looked up on its first use).
+unsigned char* noalloc_scratch() {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEV) fail(BAMG_EDEVICE, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) fail(BAMG_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    return (unsigned char*)g_scratch_ptr[dev];
+}
+
 extern "C" {
 
 void bamg_options_default(bamg_options* opt) {
@@ -2751,6 +2782,27 @@ int bamg_mlp_forward(const float* feat, int64_t n, const float* params, float* o
     });
 }
 
+int bamg_mlp_forward_noalloc(const float* feat, int64_t n, const float* params, float* out, void* stream) {
+    return run_guarded([&] {
+        if (!feat || !params || !out) fail(BAMG_EINVAL, "NULL argument");
+        if (n < 0 || n > NOALLOC_MLP_MAXN)
+            fail(BAMG_EINVAL, "n = %lld outside [0, %lld] (the points the static scratch holds)", (long long)n,
+                 NOALLOC_MLP_MAXN);
+        if (n == 0) return;
+        hipStream_t s = (hipStream_t)stream;
+        unsigned char* base = noalloc_scratch();
+        MlpPack* pk = (MlpPack*)base;
+        unsigned short* xb = (unsigned short*)(base + NOALLOC_PK_BYTES);
+        // the same launches as bamg_mlp_forward; every byte they read from
+        // the scratch is written first by this call
+        LAUNCH(k_mlp_pack, 16, BAMG_BLK, s, params, pk);
+        const long long tot = (long long)n * MLP_INP;
+        LAUNCH(k_mlp_prep, (int)((tot + BAMG_BLK - 1) / BAMG_BLK), BAMG_BLK, s, (long long)n, feat, xb);
+        const int grid = (int)std::min<long long>(1024, (n + 255) / 256);
+        LAUNCH(k_mlp_infer, grid, BAMG_BLK, s, (long long)n, (const unsigned short*)xb, (const MlpPack*)pk, out);
+        HIPCHK(hipStreamSynchronize(s));
+    });
+}
 int bamg_mlp_loss_grad(const float* feat, const float* tgt, int64_t n, const float* params, float* grad,
                        double* loss, void* stream) {
     return run_guarded([&] {
