@@ -49,26 +49,95 @@ def _traffic_from_profiles(name: str):
         return None
 
 
-def cpu_baseline(args):
-    """The oracle, untuned, on a bounded sample: the whole method on the
-    tandem queue N = 1023 (n = 1,048,576; the same 6 levels, r, rates and
-    tolerance), scaled to n = 4,194,304 by the ratio of state counts (the
-    work per level is linear in n).  BLAS limited to one thread."""
+def _host_cpu():
+    """Cores this process may run on, and the CPU model."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return avail, os.cpu_count() or avail, model
+
+
+def _oracle_run(ch, args, threads):
     from threadpoolctl import threadpool_limits
     from oracle import bamg_oracle as O
-    from paper_1004_1451_amd import chains as C
-    ch = C.tandem_queue(1023)
-    with threadpool_limits(limits=1):
+    with threadpool_limits(limits=threads):
         t0 = time.perf_counter()
-        x, info, _ = O.stationary(ch.to_scipy(), O.Grid(ch.nx, ch.ny, ch.periodic), args.r,
+        x, info, h = O.stationary(ch.to_scipy(), O.Grid(ch.nx, ch.ny, ch.periodic), args.r,
                                   O.Options(levels=args.levels), tol=args.tol, max_cycles=200)
-        dt = time.perf_counter() - t0
-    scale = 4194304 / ch.n
-    return {"value": dt * scale, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle setup+solve on tandem N=1023 (n={ch.n:,}, {args.levels} levels, r={args.r}, "
-                      f"tol={args.tol:g}, {info.cycles} cycles) took {dt:.2f} s on 1 thread; scaled by n ratio "
-                      f"{scale:.2f}",
-            "converged": bool(info.converged)}
+        return time.perf_counter() - t0, x, info, h
+
+
+def cpu_baseline(args):
+    """The oracle, untuned, on a bounded sample of the workload: the whole
+    method (same kind of chain, r, levels, tolerance) on a chain of half the
+    side (a quarter of the states: tandem N = 1023, or the 512^2 lattice),
+    once with its BLAS/LAPACK on one thread and once on every core this
+    process may use; the one-thread time is scaled to the benchmarked chain
+    by the ratio of state counts (the work per level is linear in n; the
+    coarsest SVD grows faster, so the scaled figure understates the
+    oracle)."""
+    from paper_1004_1451_amd import chains as C
+    if args.workload == "lattice":
+        ch, full, name = C.weighted_lattice(args.M // 2, seed=1), args.M * args.M, f"periodic lattice {args.M // 2}^2"
+    else:
+        ch, full, name = C.tandem_queue((args.N + 1) // 2 - 1), (args.N + 1) ** 2, f"tandem N={(args.N + 1) // 2 - 1}"
+    avail, total, model = _host_cpu()
+    dt1, _, info1, _ = _oracle_run(ch, args, 1)
+    dtn, _, _, _ = _oracle_run(ch, args, avail)
+    scale = full / ch.n
+    return {"value": round(dt1 * scale, 3), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle setup+solve on {name} (n={ch.n:,}, {args.levels} levels, r={args.r}, "
+                      f"tol={args.tol:g}, {info1.cycles} cycles): {dt1:.2f} s on 1 thread, scaled by the n ratio "
+                      f"{scale:.0f}; {dtn:.2f} s with {avail} threads",
+            "all_cores": {"threads": avail, "seconds_sample": round(dtn, 3),
+                          "value_scaled": round(dtn * scale, 3)},
+            "host": {"nproc": total, "available": avail, "cpu_model": model},
+            "converged": bool(info1.converged)}
+
+
+def oracle_full(args, x_by_form, stats_by_form, h_by_form):
+    """The oracle on the benchmarked chain itself (N = 2047, one thread), and
+    how far each GPU form is from it: ||x - x_oracle||_1, per level
+    ||B_l - B_l^oracle||_F / ||B_l^oracle||_F and the rows whose P pattern
+    differs.  Minutes of CPU time: only with --oracle-full."""
+    from paper_1004_1451_amd import chains as C
+    ch = C.tandem_queue(args.N)
+    avail, total, model = _host_cpu()
+    dt, xo, info, ho = _oracle_run(ch, args, 1)
+    out = {"oracle_seconds_1_thread": round(dt, 2), "oracle_cycles": info.cycles,
+           "oracle_residual_l1": info.residual_l1, "host": {"nproc": total, "cpu_model": model}, "forms": {}}
+    for form, x in x_by_form.items():
+        h = h_by_form[form]
+        levels = []
+        for l, lv in enumerate(ho.levels):
+            Bg = h["B"][l]
+            Bo = lv.B.tocsr()
+            rel = float(np.sqrt(((Bg - Bo).multiply(Bg - Bo)).sum() / (Bo.multiply(Bo)).sum()))
+            ent = {"n": int(Bo.shape[0]), "B_rel_fro": rel}
+            if l < len(ho.levels) - 1:
+                Pg, Po = h["P"][l].tocsr(), lv.P.tocsr()
+                Pg.sort_indices(); Po.sort_indices()
+                same = np.array_equal(Pg.indptr, Po.indptr) and np.array_equal(Pg.indices, Po.indices)
+                if same:
+                    bad = 0
+                else:
+                    rows_g = np.split(Pg.indices, Pg.indptr[1:-1])
+                    rows_o = np.split(Po.indices, Po.indptr[1:-1])
+                    bad = int(sum(not np.array_equal(a, b) for a, b in zip(rows_g, rows_o)))
+                ent["P_pattern_rows_differing"] = bad
+            levels.append(ent)
+        out["forms"][form] = {"l1_vs_oracle": float(np.abs(x - xo).sum()), "gpu_cycles": stats_by_form[form],
+                              "levels": levels}
+    return out
 
 
 def cpu_baseline_batch(chains, args, budget_s=15.0):
@@ -153,17 +222,31 @@ def _roofline(stats, traffic):
                       "bytes_per_launch": int(sweep_bytes), "mean_launch_us": round(sweep_ms * 1e3, 2)}
 
 
+def _per_launch(stats, ms_field, n_field, bytes_field):
+    """Mean HIP-event time of one launch kind (us) and its algorithmic GB/s
+    (the bytes of that same launch over its own time)."""
+    ms = sum(getattr(s, ms_field) for s in stats)
+    n = sum(getattr(s, n_field) for s in stats)
+    if n == 0 or ms <= 0:
+        return None
+    us = ms * 1e3 / n
+    b = getattr(stats[-1], bytes_field)
+    return {"us": round(us, 2), "bytes": int(b), "GBps": round(b / (us * 1e-6) / 1e9, 1),
+            "frac_of_peak": round(b / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4), "launches": n}
+
+
 def _kernel_detail(stats):
-    gal_ms = sum(s.galerkin_ms for s in stats) / max(1, sum(s.galerkin_launches for s in stats))
-    ls_ms = sum(s.lsfit_ms for s in stats) / max(1, sum(s.lsfit_launches for s in stats))
     return {
         "setup_ms": round(float(np.mean([s.t_setup_ms for s in stats])), 3),
         "solve_ms": round(float(np.mean([s.t_solve_ms for s in stats])), 3),
         "op_complexity": round(stats[-1].op_complexity, 4),
-        "galerkin_numeric_us": round(gal_ms * 1e3, 2),
-        "galerkin_GBps": round(stats[-1].galerkin_bytes / (gal_ms * 1e-3) / 1e9, 1) if gal_ms > 0 else None,
-        "lsfit_us": round(ls_ms * 1e3, 2),
-        "lsfit_GBps": round(stats[-1].lsfit_bytes / (ls_ms * 1e-3) / 1e9, 1) if ls_ms > 0 else None,
+        # level 0, one entry per launch kind: B_1 = Q (B_0 P) numeric pass,
+        # T_1 = Q P numeric pass, B_1 symbolic pass, LS fit of each setup pass
+        "galerkin_B_numeric": _per_launch(stats, "galerkin_ms", "galerkin_launches", "galerkin_bytes"),
+        "galerkin_T_numeric": _per_launch(stats, "gal_t_ms", "gal_t_launches", "gal_t_bytes"),
+        "galerkin_B_symbolic": _per_launch(stats, "gal_sym_ms", "gal_sym_launches", "gal_sym_bytes"),
+        "lsfit_first_pass": _per_launch(stats, "lsfit_ms", "lsfit_launches", "lsfit_bytes"),
+        "lsfit_recompute_pass": _per_launch(stats, "lsfit2_ms", "lsfit2_launches", "lsfit2_bytes"),
         "coarsest_min_pivot": stats[-1].coarsest_min_pivot,
         "cycle_graph": stats[-1].cycle_graph,
         "sweep_tune_ms_total": round(stats[-1].tune_ms, 2),
@@ -188,13 +271,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["tandem", "batch64", "learned", "upg"], default="tandem",
+    ap.add_argument("--workload", choices=["tandem", "lattice", "batch64", "learned", "upg"], default="tandem",
                     help="tandem: one tandem queue (default N=2047, n=4.2M); batch64: 64 mixed chains in one handle; "
                          "learned: train the interpolation network on 32 jittered tandems (untimed), then time the "
                          "learned form on the tandem queue against the plain forms")
     ap.add_argument("--train-chains", type=int, default=32)
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--N", type=int, default=2047, help="tandem queue capacity (side N+1)")
+    ap.add_argument("--M", type=int, default=1024, help="lattice workload: side of the periodic lattice")
     ap.add_argument("--levels", type=int, default=None, help="6 (tandem, learned), 3 (upg)")
     ap.add_argument("--r", type=int, default=None, help="test vectors: 12, or 6 for upg (Table 4)")
     ap.add_argument("--tol", type=float, default=None, help="1e-10, or 1e-8 for upg (Table 4)")
@@ -207,6 +291,9 @@ def main():
     ap.add_argument("--no-fp64-compare", action="store_true",
                     help="skip the untimed FP64 run that the mixed result is compared with")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-full", action="store_true",
+                    help="tandem workload: also run the oracle on the benchmarked chain itself (minutes of CPU time) "
+                         "and report each GPU form's distance from it")
     ap.add_argument("--solver", choices=["fgmres", "parnoldi", "mle"], default="fgmres",
                     help="tandem workload: FGMRES (Section 4.2), preconditioned Arnoldi (Section 4.3) or the "
                          "stand-alone MLE iteration (Section 4.1)")
@@ -219,7 +306,7 @@ def main():
     args = ap.parse_args()
     upg = args.workload == "upg"
     if args.levels is None:
-        args.levels = 3 if upg else 6
+        args.levels = 3 if upg else (5 if args.workload == "lattice" else 6)
     if args.r is None:
         args.r = 6 if upg else 12
     if args.tol is None:
@@ -246,15 +333,18 @@ def main():
         # counters of the sweep form that ran (ELL-4 copy or CSR)
         form = "k_sweep_ve" if stats[-1].sweep_ell else "k_sweep_v"
         return _traffic_from_profiles(f"{form}_{args.workload}_{args.precision}")
-    if args.workload == "tandem":
-        ch = C.tandem_queue(args.N)
+    if args.workload in ("tandem", "lattice"):
+        lattice = args.workload == "lattice"
+        # the weighted periodic lattice with seed 1 (its stationary vector is
+        # the weighted degree, known in closed form) or the tandem queue
+        ch = C.weighted_lattice(args.M, seed=1) if lattice else C.tandem_queue(args.N)
         rp, ci, v = B.device_csr(ch)
         x = torch.empty(ch.n, dtype=torch.float64, device="cuda")
         relax = B.RELAX_MCGS if args.relax == "mcgs" else B.RELAX_JACOBI
         opts = B.default_options(levels=args.levels, precision=prec, profile=1, relax=relax, mu=args.mu)
 
         def step():
-            h = B.Hierarchy(ch.n, rp, ci, v, (ch.nx, ch.ny, 0), args.r, opts)
+            h = B.Hierarchy(ch.n, rp, ci, v, (ch.nx, ch.ny, int(ch.periodic)), args.r, opts)
             if args.solver == "mle":
                 info = h.mle_iterate(x, args.tol, 200)
             else:
@@ -276,6 +366,8 @@ def main():
                        "history": [float("%.3e" % v) for v in list(infos[-1].history)[: infos[-1].history_len]],
                        "residual_l1": max(i.residual_l1 for i in infos),
                        "converged": all(i.converged for i in infos)})
+        if ch.exact is not None:
+            detail["l1_error_vs_closed_form"] = float(np.abs(x.cpu().numpy() - ch.exact).sum())
         if prec == B.MIXED and not args.no_fp64_compare:
             # outside the timed region: the plain FP64 form, its time per step
             # and how far the mixed solution is from it
@@ -285,13 +377,18 @@ def main():
             detail["fp64_ms_per_step"] = round(sec64 * 1e3, 3)
             detail["fp64_cycles"] = res64[-1][0].cycles
             detail["l1_diff_vs_fp64_path"] = float((x - x_mixed).abs().sum().item())
+            if ch.exact is not None:
+                detail["fp64_l1_error_vs_closed_form"] = float(np.abs(x.cpu().numpy() - ch.exact).sum())
         out = {
-            "metric": "setup+solve seconds to ||Bx||_1/||x||_1<=1e-10 at n=4.2M; sweep HBM GB/s",
+            "metric": ("setup+solve seconds to ||Bx||_1/||x||_1<=1e-10 on the 1024^2 weighted lattice" if lattice
+                       else "setup+solve seconds to ||Bx||_1/||x||_1<=1e-10 at n=4.2M; sweep HBM GB/s"),
             "value": round(sec, 6), "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": round(sec * 1e3, 3), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
             "dtype": "f64" if prec == B.FP64 else "f32+f64", "data": "synthetic",
-            "config": {"workload": f"tandem queue N={args.N} (n={ch.n:,}), rates 11/31,10/31,10/31, r={args.r}, "
-                                   f"{args.levels} levels, tol {args.tol:g}", "precision": args.precision,
+            "config": {"workload": (f"weighted periodic lattice {args.M}x{args.M} (n={ch.n:,}), w~U[0.1,1], "
+                                    f"r={args.r}, {args.levels} levels, tol {args.tol:g}") if lattice else
+                                   (f"tandem queue N={args.N} (n={ch.n:,}), rates 11/31,10/31,10/31, r={args.r}, "
+                                    f"{args.levels} levels, tol {args.tol:g}"), "precision": args.precision,
                        **({"relax": "multicolour Gauss-Seidel"} if args.relax == "mcgs" else {}),
                        **({"solver": {"parnoldi": "preconditioned Arnoldi", "mle": "MLE iteration"}[args.solver]}
                           if args.solver != "fgmres" else {}),
@@ -300,6 +397,29 @@ def main():
         }
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline(args)
+        if args.oracle_full and not lattice:
+            import scipy.sparse as sps
+            xs, cyc, hs = {}, {}, {}
+            for form, pr in (("mixed", B.MIXED), ("fp64", B.FP64)):
+                hh = B.Hierarchy(ch.n, rp, ci, v, (ch.nx, ch.ny, int(ch.periodic)), args.r,
+                                 B.default_options(levels=args.levels, precision=pr))
+                info = hh.solve(x, args.tol, 200)
+                xs[form], cyc[form] = x.cpu().numpy().copy(), info.cycles
+                Bs, Ps = [], []
+                for l in range(args.levels):
+                    li = hh.level_info(l)
+                    Bs.append(sps.csr_matrix((hh.export(l, B.X_B_VAL), hh.export(l, B.X_B_COL),
+                                              hh.export(l, B.X_B_ROWPTR)), shape=(li.n, li.n)))
+                    if l + 1 < args.levels:
+                        nc = hh.level_info(l + 1).n
+                        pc = hh.export(l, B.X_P_COL).reshape(-1, 4)
+                        pv = hh.export(l, B.X_P_VAL).reshape(-1, 4)
+                        ok = pc >= 0
+                        rows = np.repeat(np.arange(li.n), 4).reshape(-1, 4)[ok]
+                        Ps.append(sps.csr_matrix((pv[ok], (rows, pc[ok])), shape=(li.n, nc)))
+                hs[form] = {"B": Bs, "P": Ps}
+                hh.close()
+            out["oracle_full"] = oracle_full(args, xs, cyc, hs)
     elif upg:
         ch = C.upg(args.upg_n, seed=0)
         rp, ci, v = B.device_csr(ch)

@@ -174,8 +174,10 @@ typedef struct {
     double op_complexity;   /* sum nnz(B_l) / nnz(B_0)                         */
     double coarsest_min_pivot; /* min |pivot| / column max in the coarsest inverse */
     double t_setup_ms, t_solve_ms;   /* host wall clock of the last calls      */
-    /* with options.profile: HIP-event time of the level-0 test-vector sweeps
-       (every launch) and Galerkin numeric products, and their launch counts */
+    /* with options.profile: HIP-event time and launch count of the level-0
+       test-vector sweeps (every launch), of the numeric pass of the Galerkin
+       product B_1 = Q (B_0 P) and of the least-squares fit of the first
+       setup pass, each with the algorithmic bytes of one such launch */
     double sweep_ms, galerkin_ms, lsfit_ms;
     int32_t sweep_launches, galerkin_launches, lsfit_launches;
     int64_t sweep_bytes, galerkin_bytes, lsfit_bytes; /* algorithmic bytes per launch */
@@ -198,6 +200,12 @@ typedef struct {
     int32_t sweep_ell;      /* 1: the level-0 sweeps, the cycle's level-0 residual
                                and the outer SpMV read a 4-wide ELL copy of B_0
                                (every row has at most 4 entries)            */
+    /* with options.profile, the other level-0 launches of the setup, same
+       form: the numeric pass of T_1 = Q (T_0 P) (T_0 = I), the symbolic pass
+       of B_1 and the least-squares fit of the recompute pass (U and V) */
+    double gal_t_ms, gal_sym_ms, lsfit2_ms;
+    int32_t gal_t_launches, gal_sym_launches, lsfit2_launches;
+    int64_t gal_t_bytes, gal_sym_bytes, lsfit2_bytes;
 } bamg_stats;
 
 typedef struct {

@@ -471,7 +471,7 @@ struct Engine : bamg_ctx {
     double* learn_acc = nullptr;
     int learn_grid = 0;
     // profiling
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_sweep, ev_gal, ev_ls, ev_gj;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_sweep, ev_gal, ev_ls, ev_gj, ev_gal_t, ev_gal_sym, ev_ls2;
     double gj_flops = 0;             // flops of the profiled dense updates
     // FGMRES: chain flags after each Arnoldi step, read by the host one step
     // late (pinned, two slots), the events that mark them, the inner
@@ -488,7 +488,7 @@ struct Engine : bamg_ctx {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cap_s) (void)hipStreamDestroy(cap_s);
-        for (auto* v : {&ev_sweep, &ev_gal, &ev_ls, &ev_gj})
+        for (auto* v : {&ev_sweep, &ev_gal, &ev_ls, &ev_gj, &ev_gal_t, &ev_gal_sym, &ev_ls2})
             for (auto& p : *v) { event_pool().put(p.first); event_pool().put(p.second); }
         A.release();
     }
@@ -1077,15 +1077,17 @@ struct Engine : bamg_ctx {
             const EllSrc es = which == 0 ? ell_of(l) : EllSrc{nullptr, nullptr, 0, EF_CSR};
             ef_dispatch(es.ef, [&](auto efc) {
                 constexpr int EF = decltype(efc)::value;
+                std::pair<hipEvent_t, hipEvent_t> ev;
+                if (profile && which == 0) ev = ev_begin();
                 LAUNCH(k_galerkin_symbolic<EF>, gb, GAL_THREADS, s, nc, (const ChainGeo*)c.dgeo, c.nch, f.qc, M.rp,
                        M.ci, es.c, es.ld, f.pc, f.cnt, f.mask);
+                if (profile && which == 0) ev_end(ev, ev_gal_sym);
                 scan(nc, f.cnt, Cm.rp);
-                std::pair<hipEvent_t, hipEvent_t> ev;
                 if (profile) ev = ev_begin();
                 LAUNCH((k_galerkin_numeric<T, EF>), gb, GAL_THREADS, s, nc, (const ChainGeo*)c.dgeo, c.nch, f.qc,
                        (const T*)f.qv, M.rp, M.ci, (const T*)M.v, es.c, es.v, es.ld, f.pc, (const T*)f.pv, f.mask,
                        Cm.rp, Cm.ci, Cm.v);
-                if (profile) ev_end(ev, ev_gal);
+                if (profile) ev_end(ev, which == 0 ? ev_gal : ev_gal_t);
             });
         }
         zero(err, sizeof(int) * 4);
@@ -1141,7 +1143,7 @@ struct Engine : bamg_ctx {
                    (const int*)lv.B.ci, (const T*)lv.B.v, use_v ? (float*)nullptr : lv.feat,
                    use_v ? lv.slotw : lv.slotw0);
         }
-        if (profile) ev_end(ev, ev_ls);
+        if (profile) ev_end(ev, use_v ? ev_ls2 : ev_ls);
         LAUNCH(k_build_q<T>, nblk(c.rows), BAMG_BLK, s, c.rows, (const ChainGeo*)c.dgeo, (const ChainGeo*)lv.dgeo, c.nch,
                lv.pc, lv.qc, lv.qv, lv.qmask);
         galerkin(l, profile);
@@ -1779,7 +1781,9 @@ struct Engine : bamg_ctx {
         const int nl = (int)L.size();
         for (int l = 0; l < nl; ++l) LAUNCH(k_copy_int, 1, BAMG_WAVE, s, (const int*)(L[l].B.rp + L[l].rows), gath + l);
         LAUNCH(k_copy_int, 1, BAMG_WAVE, s, (const int*)derr, gath + nl);
-        std::vector<int> g = getn(gath, (size_t)nl + 1);
+        const bool t1 = nl > 1 && L[1].Tm.rp;
+        if (t1) LAUNCH(k_copy_int, 1, BAMG_WAVE, s, (const int*)(L[1].Tm.rp + L[1].rows), gath + nl + 1);
+        std::vector<int> g = getn(gath, (size_t)nl + (t1 ? 2 : 1));
         if (g[nl]) fail(BAMG_EDEVICE, "a coarse grid operator has a row outside the 3 x 3 box");
         long long tot = 0;
         for (int l = 0; l < nl; ++l) tot += g[l];
@@ -1802,7 +1806,10 @@ struct Engine : bamg_ctx {
             st.mlp_fallback = (int64_t)la[1];
         }
         acc(ev_gal, st.galerkin_ms, st.galerkin_launches);
+        acc(ev_gal_t, st.gal_t_ms, st.gal_t_launches);
+        acc(ev_gal_sym, st.gal_sym_ms, st.gal_sym_launches);
         acc(ev_ls, st.lsfit_ms, st.lsfit_launches);
+        acc(ev_ls2, st.lsfit2_ms, st.lsfit2_launches);
         acc(ev_gj, st.dense_update_ms, st.dense_update_launches);
         st.dense_update_flops = gj_flops;
         gj_flops = 0;
@@ -1816,11 +1823,23 @@ struct Engine : bamg_ctx {
         st.sweep_ell = L[0].B.eci ? 1 : 0;
         if (L[0].B.eci && !mcgs)         // the ELL-4 copy: 4 entries per row, no row pointers
             st.sweep_bytes = 4LL * n0 * (4 + vb) + n0 * vb + 2LL * n0 * r * vb;
-        if (L.size() > 1) {
-            long long nc = L[1].rows;
-            st.galerkin_bytes = nc * 9 * (4 + vb) + (long long)(n0 + 1) * 4 + (long long)nnz0 * (4 + vb) +
-                                n0 * 4 * (4 + vb) + (nc + 1) * 4 + nc * 9 * (4 + vb);
-            st.lsfit_bytes = n0 * (long long)(r + nvmax) * vb + n0 * 4 * (4 + vb);
+        if (L.size() > 1 && !unstructured) {
+            // every array once (neighbour re-reads served from cache): Q
+            // (ELL-9 columns and values), B_0's rows (ELL-4 copy or CSR),
+            // P (ELL-4), the box masks and row pointers of the product, and
+            // the product's stored entries
+            const long long nc = L[1].rows, nnzb1 = g[1];
+            const long long nnzt1 = t1 ? g[nl + 1] : 0;
+            const long long q = nc * 9 * (4 + vb), pb = n0 * 4 * (4 + vb), ctl = nc * 2 + (nc + 1) * 4;
+            const long long brows = L[0].B.eci ? 4LL * n0 * (4 + vb) : (n0 + 1) * 4 + (long long)nnz0 * (4 + vb);
+            const long long bcols = L[0].B.eci ? 4LL * n0 * 4 : (n0 + 1) * 4 + (long long)nnz0 * 4;
+            st.galerkin_bytes = q + brows + pb + ctl + nnzb1 * (4 + vb);
+            st.gal_t_bytes = q + pb + ctl + nnzt1 * (4 + vb);
+            st.gal_sym_bytes = nc * 9 * 4 + bcols + n0 * 4 * 4 + nc * 4 + nc * 2;
+            // the fit reads the test vectors, writes P (ELL-4) and |J_i|;
+            // the first pass also injects U on the coarse points
+            st.lsfit_bytes = n0 * (long long)r * vb + pb + n0 + nc * (long long)r * vb;
+            st.lsfit2_bytes = n0 * (long long)(r + nvmax) * vb + pb + n0;
         }
     }
 
