@@ -109,10 +109,16 @@ def oracle_full(args, x_by_form, stats_by_form, h_by_form):
     how far each GPU form is from it: ||x - x_oracle||_1, per level
     ||B_l - B_l^oracle||_F / ||B_l^oracle||_F and the rows whose P pattern
     differs.  Minutes of CPU time: only with --oracle-full."""
+    from oracle import bamg_oracle as O
     from paper_1004_1451_amd import chains as C
     ch = C.tandem_queue(args.N)
     avail, total, model = _host_cpu()
-    dt, xo, info, ho = _oracle_run(ch, args, 1)
+    t0 = time.perf_counter()
+    O.PROGRESS = lambda msg: print(f"oracle: {msg} ({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    try:
+        dt, xo, info, ho = _oracle_run(ch, args, 1)
+    finally:
+        O.PROGRESS = None
     out = {"oracle_seconds_1_thread": round(dt, 2), "oracle_cycles": info.cycles,
            "oracle_residual_l1": info.residual_l1, "host": {"nproc": total, "cpu_model": model}, "forms": {}}
     for form, x in x_by_form.items():

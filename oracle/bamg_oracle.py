@@ -771,6 +771,11 @@ class Hierarchy:
     first_pass: list = field(default_factory=list)   # (P, B, T) of the down-leg
 
 
+# Optional progress report: a callable taking one string, called after each
+# level is built (long runs print through it; no effect on any result).
+PROGRESS = None
+
+
 def build_level(lv: Level, X: np.ndarray, opts: Options):
     """One level of the hierarchy from test set X: weights, LS fit, Q,
     B_{l+1}, T_{l+1} (Algorithm 3)."""
@@ -779,6 +784,8 @@ def build_level(lv: Level, X: np.ndarray, opts: Options):
     Q = averaging_q(P)
     Bc = galerkin(Q, lv.B, P)
     Tc = galerkin(Q, lv.T, P)
+    if PROGRESS is not None:
+        PROGRESS(f"level of {lv.B.shape[0]} rows built from {X.shape[1]} test vectors")
     return P, Q, J, Bc, Tc
 
 
