@@ -2504,6 +2504,12 @@ int setup_common(int32_t nchains, const int64_t* off, const int32_t* row_ptr, co
         if (off[0] != 0) fail(BAMG_EINVAL, "chain_row_off[0] must be 0");
         const long long n = off[nchains];
         if (n < 1 || n > (1LL << 30)) fail(BAMG_EINVAL, "n = %lld out of range", n);
+        // the relaxation kernels number their (row, test-vector column) pairs
+        // in 32 bits: n times the widest test set (r + up to 8 eigenvector
+        // columns) must stay below 2^31
+        if (n * (long long)(r + 8) >= (1LL << 31))
+            fail(BAMG_EUNSUPPORTED, "n * (r + 8) = %lld exceeds the 2^31 (row, column) pairs the sweeps index",
+                 n * (long long)(r + 8));
         bamg_options o;
         if (opt) o = *opt; else bamg_options_default(&o);
         check_options(o);

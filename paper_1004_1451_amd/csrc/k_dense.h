@@ -471,13 +471,17 @@ __global__ void k_normalize_into(int n, const double* __restrict__ u, const doub
 // ---------------------------------------------------------------- Hessenberg eigensolver
 // Eigenpairs of the m x m Hessenberg matrix H_m of the Arnoldi process, with
 // one wavefront (64 lanes, m <= 64), data in LDS.
-//  - Eigenvalues: Francis double-shift QR iteration (implicit bulge chase with
-//    3x3 Householder reflectors; deflation when a subdiagonal entry falls
-//    below eps times its diagonal neighbours; exceptional shifts after 10 and
-//    20 stagnant iterations).  The scalar control flow runs redundantly in
-//    every lane; the row and column updates of each reflector are spread over
-//    the lanes (lane j owns column j of a row update, lane i row i of a
-//    column update).
+//  - Eigenvalues: the Francis double-shift QR iteration of Golub and Van
+//    Loan, Matrix Computations, Algorithms 7.5.1 (the implicit double-shift
+//    step) and 7.5.2 (deflation of negligible subdiagonal entries), applied
+//    to the active unreduced window only (no Schur vectors are needed).
+//    The bulge is chased with 3-element Householder reflectors; lane j
+//    updates column j of the reflected rows and lane i row i of the
+//    reflected columns; the next reflector's vector comes from the lanes
+//    that produced it (v_readlane), not from LDS.  A window that has not
+//    deflated after 8 steps takes one step with an exceptional real double
+//    shift (both shifts at the bottom diagonal entry moved by the size of
+//    the two bottom subdiagonal entries); 40 m steps in all is a failure.
 //  - Eigenvectors of the selected eigenvalues: inverse iteration with the
 //    complex matrix H - theta I (Gaussian elimination with pivoting between
 //    adjacent rows, tiny pivots replaced by 1e-14 ||H||).
@@ -486,167 +490,135 @@ __global__ void k_normalize_into(int n, const double* __restrict__ u, const doub
 
 __device__ __forceinline__ void lds_sync() { __syncthreads(); }
 
-__device__ void hqr_wave(int m, double* A, double* wr, double* wi, int* fail) {
+// Householder vector of a 3-vector (x, y, z) (z = 0 for a 2-vector): with
+// a = -sign(x) ||(x, y, z)||, u = (x - a, y, z) and beta = 2 / u^T u, the
+// reflector I - beta u u^T maps (x, y, z) to (a, 0, 0).  beta = 0 when the
+// vector is already zero below its first entry.
+__device__ __forceinline__ void house3(double x, double y, double z, double& u0, double& u1, double& u2,
+                                       double& beta) {
+    const double tail = y * y + z * z;
+    if (tail == 0.0) { u0 = 1.0; u1 = 0.0; u2 = 0.0; beta = 0.0; return; }
+    const double nrm = sqrt(x * x + tail);
+    const double a = x >= 0.0 ? -nrm : nrm;
+    u0 = x - a; u1 = y; u2 = z;
+    beta = 2.0 / (u0 * u0 + tail);
+}
+
+// Eigenvalues of the m x m upper Hessenberg A (LDS, row-major, ld HQR_LD;
+// overwritten) into (wr, wi); *fail = 1 if the iteration does not settle.
+__device__ void francis_eigvals_wave(int m, double* A, double* wr, double* wi, int* fail) {
     const int lane = threadIdx.x;
-    const double eps = 2.220446049250313e-16;
-#define AA(i, j) A[(i) * HQR_LD + (j)]
-    double anorm = 0;
-    for (int i = 0; i < m; ++i)
-        for (int j = (i > 0 ? i - 1 : 0); j < m; ++j) anorm += fabs(AA(i, j));
-    int nn = m - 1;
-    double t = 0.0;
-    int its_total = 0;
-    while (nn >= 0) {
-        int its = 0, l;
-        do {
-            // l = the largest index in [1, nn] with a negligible subdiagonal
-            // entry (0 if none): every lane tests its own row at once
-            {
-                bool small = false;
-                if (lane >= 1 && lane <= nn) {
-                    double s = fabs(AA(lane - 1, lane - 1)) + fabs(AA(lane, lane));
-                    if (s == 0.0) s = anorm;
-                    small = fabs(AA(lane, lane - 1)) <= eps * s;
-                }
-                const unsigned long long mk = __ballot(small);
-                l = mk ? 63 - __clzll(mk) : 0;
+    const double u = 2.220446049250313e-16;
+#define HA(i, j) A[(i) * HQR_LD + (j)]
+    // scale for the zero-sum fallback of the deflation test: sum of |entries|
+    double fro = 0.0;
+    if (lane < m)
+        for (int i = 0; i <= min(lane + 1, m - 1); ++i) fro += fabs(HA(i, lane));
+#pragma unroll
+    for (int o = BAMG_WAVE / 2; o >= 1; o >>= 1) fro += __shfl_xor(fro, o, BAMG_WAVE);
+    int hi = m - 1, stuck = 0, steps = 0;
+    while (hi >= 0) {
+        lds_sync();
+        // lo: the bottom of the last negligible subdiagonal entry in the
+        // window (GVL: |h_{i,i-1}| <= u (|h_{i-1,i-1}| + |h_ii|)); every lane
+        // tests its own row, a ballot takes the largest
+        int lo;
+        {
+            bool neg = false;
+            if (lane >= 1 && lane <= hi) {
+                double d = fabs(HA(lane - 1, lane - 1)) + fabs(HA(lane, lane));
+                if (d == 0.0) d = fro;
+                neg = fabs(HA(lane, lane - 1)) <= u * d;
             }
-            lds_sync();
-            if (l >= 1 && lane == 0) AA(l, l - 1) = 0.0;
-            lds_sync();
-            double x = AA(nn, nn);
-            if (l == nn) {
-                if (lane == 0) { wr[nn] = x + t; wi[nn] = 0.0; }
-                --nn;
-            } else {
-                double y = AA(nn - 1, nn - 1);
-                double w = AA(nn, nn - 1) * AA(nn - 1, nn);
-                if (l == nn - 1) {
-                    double p = 0.5 * (y - x), q = p * p + w, z = sqrt(fabs(q));
-                    x += t;
-                    if (lane == 0) {
-                        if (q >= 0.0) {
-                            z = p + (p >= 0 ? fabs(z) : -fabs(z));
-                            wr[nn - 1] = wr[nn] = x + z;
-                            if (z != 0.0) wr[nn] = x - w / z;
-                            wi[nn - 1] = wi[nn] = 0.0;
-                        } else {
-                            wr[nn - 1] = wr[nn] = x + p;
-                            wi[nn - 1] = -z; wi[nn] = z;
-                        }
-                    }
-                    nn -= 2;
+            const unsigned long long bal = __ballot(neg);
+            lo = bal ? 63 - __clzll(bal) : 0;
+        }
+        if (lo == hi) {                          // a 1 x 1 block has deflated
+            if (lane == 0) { wr[hi] = HA(hi, hi); wi[hi] = 0.0; }
+            hi -= 1; stuck = 0;
+            continue;
+        }
+        if (lo == hi - 1) {                      // a 2 x 2 block: its eigenvalues
+            const double a = HA(hi - 1, hi - 1), b = HA(hi - 1, hi), c = HA(hi, hi - 1), d = HA(hi, hi);
+            const double mid = 0.5 * (a + d), half = 0.5 * (a - d);
+            const double disc = half * half + b * c;
+            if (lane == 0) {
+                if (disc >= 0.0) {
+                    // the root of larger modulus first, the other from the
+                    // determinant (no cancellation)
+                    const double big = mid + (mid >= 0.0 ? sqrt(disc) : -sqrt(disc));
+                    wr[hi - 1] = big;
+                    wr[hi] = big != 0.0 ? (a * d - b * c) / big : 0.0;
+                    wi[hi - 1] = wi[hi] = 0.0;
                 } else {
-                    if (its >= 60 || its_total > 60 * m) { *fail = 1; lds_sync(); return; }
-                    if (its == 10 || its == 20) {
-                        t += x;
-                        lds_sync();
-                        if (lane <= nn) AA(lane, lane) -= x;
-                        lds_sync();
-                        double s = fabs(AA(nn, nn - 1)) + fabs(AA(nn - 1, nn - 2));
-                        y = x = 0.75 * s;
-                        w = -0.4375 * s * s;
-                    }
-                    ++its; ++its_total;
-                    // mm: the largest index in [l, nn-2] where the double
-                    // shift's first column makes the subdiagonal entry
-                    // (mm, mm-1) negligible (l when none does).  Each lane
-                    // evaluates its own candidate mm = lane, with the
-                    // arithmetic of a scan from nn-2 downwards; a ballot
-                    // takes the scan's first hit.
-                    int mm;
-                    double p = 0, q = 0, r = 0;
-                    {
-                        bool ok = false;
-                        const int mc = lane;
-                        if (mc >= l && mc <= nn - 2) {
-                            const double z = AA(mc, mc);
-                            r = x - z;
-                            double s = y - z;
-                            p = (r * s - w) / AA(mc + 1, mc) + AA(mc, mc + 1);
-                            q = AA(mc + 1, mc + 1) - z - r - s;
-                            r = AA(mc + 2, mc + 1);
-                            s = fabs(p) + fabs(q) + fabs(r);
-                            p /= s; q /= s; r /= s;
-                            if (mc == l) {
-                                ok = true;
-                            } else {
-                                const double u = fabs(AA(mc, mc - 1)) * (fabs(q) + fabs(r));
-                                const double v = fabs(p) * (fabs(AA(mc - 1, mc - 1)) + fabs(z) + fabs(AA(mc + 1, mc + 1)));
-                                ok = u <= eps * v;
-                            }
-                        }
-                        const unsigned long long mk = __ballot(ok);
-                        mm = 63 - __clzll(mk);
-                        p = readlane_f64(p, mm);
-                        q = readlane_f64(q, mm);
-                        r = readlane_f64(r, mm);
-                    }
-                    lds_sync();
-                    if (lane >= mm + 2 && lane <= nn) {
-                        AA(lane, lane - 2) = 0.0;
-                        if (lane != mm + 2) AA(lane, lane - 3) = 0.0;
-                    }
-                    lds_sync();
-                    for (int k = mm; k <= nn - 1; ++k) {
-                        if (k != mm) {
-                            p = AA(k, k - 1);
-                            q = AA(k + 1, k - 1);
-                            r = (k != nn - 1) ? AA(k + 2, k - 1) : 0.0;
-                            x = fabs(p) + fabs(q) + fabs(r);
-                            if (x == 0.0) continue;
-                            const double ix = cz_recip(x);
-                            p *= ix; q *= ix; r *= ix;
-                        }
-                        double s = sqrt(p * p + q * q + r * r);
-                        if (p < 0) s = -s;
-                        lds_sync();
-                        if (lane == 0) {
-                            if (k == mm) {
-                                if (l != mm) AA(k, k - 1) = -AA(k, k - 1);
-                            } else {
-                                AA(k, k - 1) = -s * x;
-                            }
-                        }
-                        p += s;
-                        const double is = cz_recip(s), ip = cz_recip(p);
-                        double hx = p * is, hy = q * is, hz = r * is;
-                        double qq = q * ip, rr = r * ip;
-                        lds_sync();
-                        {   // rows k..k+2, columns k..nn
-                            int j = lane;
-                            if (j >= k && j <= nn) {
-                                double pp = AA(k, j) + qq * AA(k + 1, j);
-                                if (k != nn - 1) {
-                                    pp += rr * AA(k + 2, j);
-                                    AA(k + 2, j) -= pp * hz;
-                                }
-                                AA(k + 1, j) -= pp * hy;
-                                AA(k, j) -= pp * hx;
-                            }
-                        }
-                        lds_sync();
-                        {   // columns k..k+2, rows l..min(nn, k+3)
-                            int mmin = nn < k + 3 ? nn : k + 3;
-                            int i = lane;
-                            if (i >= l && i <= mmin) {
-                                double pp = hx * AA(i, k) + hy * AA(i, k + 1);
-                                if (k != nn - 1) {
-                                    pp += hz * AA(i, k + 2);
-                                    AA(i, k + 2) -= pp * rr;
-                                }
-                                AA(i, k + 1) -= pp * qq;
-                                AA(i, k) -= pp;
-                            }
-                        }
-                        lds_sync();
-                    }
+                    const double im = sqrt(-disc);
+                    wr[hi - 1] = wr[hi] = mid;
+                    wi[hi - 1] = im; wi[hi] = -im;
+                }
+            }
+            hi -= 2; stuck = 0;
+            continue;
+        }
+        if (++steps > 40 * m) { if (lane == 0) *fail = 1; lds_sync(); return; }
+        // the double shift: eigenvalues of the trailing 2 x 2 block through
+        // their sum s and product t, or the exceptional pair
+        double s, t;
+        if (++stuck % 8 == 0) {
+            const double r = HA(hi, hi) + fabs(HA(hi, hi - 1)) + fabs(HA(hi - 1, hi - 2));
+            s = 2.0 * r; t = r * r;
+        } else {
+            const double a = HA(hi - 1, hi - 1), b = HA(hi - 1, hi), c = HA(hi, hi - 1), d = HA(hi, hi);
+            s = a + d; t = a * d - b * c;
+        }
+        // first column of (H - sigma_1 I)(H - sigma_2 I) on the window
+        const double h00 = HA(lo, lo), h01 = HA(lo, lo + 1), h10 = HA(lo + 1, lo), h11 = HA(lo + 1, lo + 1);
+        double x = h00 * h00 + h01 * h10 - s * h00 + t;
+        double y = h10 * (h00 + h11 - s);
+        double z = h10 * HA(lo + 2, lo + 1);
+        lds_sync();
+        for (int k = lo; k <= hi - 1; ++k) {
+            const bool two = k == hi - 1;        // the last reflector spans 2 rows
+            double u0, u1, u2, beta;
+            house3(x, y, two ? 0.0 : z, u0, u1, u2, beta);
+            // rows k .. k+2 from the left, columns max(lo, k-1) .. hi
+            {
+                const int j = lane;
+                if (j >= max(lo, k - 1) && j <= hi) {
+                    const double a0 = HA(k, j), a1 = HA(k + 1, j), a2 = two ? 0.0 : HA(k + 2, j);
+                    const double w = beta * (u0 * a0 + u1 * a1 + u2 * a2);
+                    HA(k, j) = a0 - w * u0;
+                    HA(k + 1, j) = a1 - w * u1;
+                    if (!two) HA(k + 2, j) = a2 - w * u2;
                 }
             }
             lds_sync();
-        } while (l < nn - 1);
+            // columns k .. k+2 from the right, rows lo .. min(k+3, hi)
+            double c0 = 0.0;
+            {
+                const int i = lane;
+                if (i >= lo && i <= min(k + 3, hi)) {
+                    const double a0 = HA(i, k), a1 = HA(i, k + 1), a2 = two ? 0.0 : HA(i, k + 2);
+                    const double w = beta * (a0 * u0 + a1 * u1 + a2 * u2);
+                    c0 = a0 - w * u0;
+                    HA(i, k) = c0;
+                    HA(i, k + 1) = a1 - w * u1;
+                    if (!two) HA(i, k + 2) = a2 - w * u2;
+                }
+            }
+            // next reflector: column k below the diagonal, rows k+1 .. k+3
+            if (!two) {
+                x = readlane_f64(c0, k + 1);
+                y = readlane_f64(c0, k + 2);
+                z = k + 3 <= hi ? readlane_f64(c0, k + 3) : 0.0;
+            }
+            lds_sync();
+            // entries the reflector annihilated: exactly zero below the
+            // subdiagonal of column k - 1 (k > lo)
+            if (k > lo && (lane == k + 1 || lane == k + 2) && lane <= hi) HA(lane, k - 1) = 0.0;
+        }
     }
-#undef AA
+    lds_sync();
+#undef HA
 }
 
 // Packed upper triangle (complex): row k, column j >= k.
@@ -777,7 +749,7 @@ __device__ void hessenberg_eig_body(int m, int want, const double* __restrict__ 
     if (lane < HQR_MAXM) used[lane] = 0;
     __threadfence_block();
     lds_sync();
-    hqr_wave(m, A, wr, wi, &fail);
+    francis_eigvals_wave(m, A, wr, wi, &fail);
     lds_sync();
     int taken = 0, ne = 0, ncols = 0;
     while (taken < want && !fail) {
@@ -859,7 +831,7 @@ __device__ void hessenberg_near_zero_body(int k, const double* __restrict__ Hh, 
     for (int off = BAMG_WAVE / 2; off > 0; off >>= 1) hn = fmax(hn, __shfl_xor(hn, off, BAMG_WAVE));
     __threadfence_block();
     lds_sync();
-    hqr_wave(k, A, wr, wi, &fail);
+    francis_eigvals_wave(k, A, wr, wi, &fail);
     lds_sync();
     int best = 0;
     double bm = wr[0] * wr[0] + wi[0] * wi[0];

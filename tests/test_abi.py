@@ -70,3 +70,18 @@ def test_struct_layouts_match_header(tmp_path):
         py = structs[cname]
         got = C.sizeof(py) if what == "size" else getattr(py, what).offset
         assert got == int(val), (cname, what, got, val)
+
+
+def test_size_limit_is_refused_before_any_launch():
+    # n (r + 8) >= 2^31 (row, column) pairs: refused on the host with
+    # EUNSUPPORTED before any device work (dummy non-NULL pointers are never
+    # dereferenced)
+    import ctypes as C
+    lib = B.load()
+    h = C.c_void_p()
+    fake = C.c_void_p(16)
+    n = (1 << 30) - 4
+    ny = 2
+    rc = lib.bamg_setup(n, fake, fake, fake, B.Grid(n // ny, ny, 0), 12, None, None, C.byref(h))
+    assert rc == B.EUNSUPPORTED
+    assert b"2^31" in lib.bamg_last_error()
