@@ -246,11 +246,10 @@ def _kernel_detail(stats):
         "setup_ms": round(float(np.mean([s.t_setup_ms for s in stats])), 3),
         "solve_ms": round(float(np.mean([s.t_solve_ms for s in stats])), 3),
         "op_complexity": round(stats[-1].op_complexity, 4),
-        # level 0, one entry per launch kind: B_1 = Q (B_0 P) numeric pass,
-        # T_1 = Q P numeric pass, B_1 symbolic pass, LS fit of each setup pass
-        "galerkin_B_numeric": _per_launch(stats, "galerkin_ms", "galerkin_launches", "galerkin_bytes"),
-        "galerkin_T_numeric": _per_launch(stats, "gal_t_ms", "gal_t_launches", "gal_t_bytes"),
-        "galerkin_B_symbolic": _per_launch(stats, "gal_sym_ms", "gal_sym_launches", "gal_sym_bytes"),
+        # level 0, one entry per launch kind: both Galerkin products
+        # (B_1, T_1) in one launch, their copy into CSR, LS fit of each pass
+        "galerkin_BT": _per_launch(stats, "galerkin_ms", "galerkin_launches", "galerkin_bytes"),
+        "galerkin_csr": _per_launch(stats, "gal_csr_ms", "gal_csr_launches", "gal_csr_bytes"),
         "lsfit_first_pass": _per_launch(stats, "lsfit_ms", "lsfit_launches", "lsfit_bytes"),
         "lsfit_recompute_pass": _per_launch(stats, "lsfit2_ms", "lsfit2_launches", "lsfit2_bytes"),
         "coarsest_min_pivot": stats[-1].coarsest_min_pivot,

@@ -175,9 +175,10 @@ typedef struct {
     double coarsest_min_pivot; /* min |pivot| / column max in the coarsest inverse */
     double t_setup_ms, t_solve_ms;   /* host wall clock of the last calls      */
     /* with options.profile: HIP-event time and launch count of the level-0
-       test-vector sweeps (every launch), of the numeric pass of the Galerkin
-       product B_1 = Q (B_0 P) and of the least-squares fit of the first
-       setup pass, each with the algorithmic bytes of one such launch */
+       test-vector sweeps (every launch), of the launch that forms both
+       Galerkin products B_1 = Q (B_0 P) and T_1 = Q (T_0 P) (T_0 = I) and of
+       the least-squares fit of the first setup pass, each with the
+       algorithmic bytes of one such launch */
     double sweep_ms, galerkin_ms, lsfit_ms;
     int32_t sweep_launches, galerkin_launches, lsfit_launches;
     int64_t sweep_bytes, galerkin_bytes, lsfit_bytes; /* algorithmic bytes per launch */
@@ -201,11 +202,11 @@ typedef struct {
                                and the outer SpMV read a 4-wide ELL copy of B_0
                                (every row has at most 4 entries)            */
     /* with options.profile, the other level-0 launches of the setup, same
-       form: the numeric pass of T_1 = Q (T_0 P) (T_0 = I), the symbolic pass
-       of B_1 and the least-squares fit of the recompute pass (U and V) */
-    double gal_t_ms, gal_sym_ms, lsfit2_ms;
-    int32_t gal_t_launches, gal_sym_launches, lsfit2_launches;
-    int64_t gal_t_bytes, gal_sym_bytes, lsfit2_bytes;
+       form: the copy of both products from their ELL-9 form into CSR, and
+       the least-squares fit of the recompute pass (U and V) */
+    double gal_csr_ms, lsfit2_ms;
+    int32_t gal_csr_launches, lsfit2_launches;
+    int64_t gal_csr_bytes, lsfit2_bytes;
 } bamg_stats;
 
 typedef struct {

@@ -77,9 +77,8 @@ class Stats(C.Structure):
                 ("sweep_vw", C.c_int32), ("sweep_bs", C.c_int32), ("tune_ms", C.c_double),
                 ("mlp_points", C.c_int64), ("mlp_fallback", C.c_int64), ("dense_update_ms", C.c_double),
                 ("dense_update_launches", C.c_int32), ("dense_update_flops", C.c_double),
-                ("sweep_ell", C.c_int32), ("gal_t_ms", C.c_double), ("gal_sym_ms", C.c_double),
-                ("lsfit2_ms", C.c_double), ("gal_t_launches", C.c_int32), ("gal_sym_launches", C.c_int32),
-                ("lsfit2_launches", C.c_int32), ("gal_t_bytes", C.c_int64), ("gal_sym_bytes", C.c_int64),
+                ("sweep_ell", C.c_int32), ("gal_csr_ms", C.c_double), ("lsfit2_ms", C.c_double),
+                ("gal_csr_launches", C.c_int32), ("lsfit2_launches", C.c_int32), ("gal_csr_bytes", C.c_int64),
                 ("lsfit2_bytes", C.c_int64)]
 
 

@@ -323,9 +323,11 @@ struct Csr {
     T* v = nullptr;
     int* eci = nullptr;              // ELL-4 copy (rows of at most 4 entries), or null
     T* ev = nullptr;
-    int* cci = nullptr;              // column-major ELL-9 copy (coarse grid levels), or null
-    T* cv = nullptr;
+    int* cci = nullptr;              // column-major ELL-9 copy (coarse grid levels) the kernels
+    T* cv = nullptr;                 // read, or null (BAMG_SWEEP_ELL=0)
     int cld = 0;                     // its stride (the level's rows)
+    int* gci = nullptr;              // the ELL-9 arrays the Galerkin product writes
+    T* gv = nullptr;                 // (coarse grid levels; cci / cv alias them)
 };
 
 // Rows of one level: all present chains, continuing chains first.
@@ -346,13 +348,13 @@ struct Level {
     T* U = nullptr;                  // rows x r relaxed test vectors
     T* V = nullptr;                  // rows x VS eigenvector approximations
     T *e = nullptr, *e2 = nullptr, *f = nullptr, *r = nullptr;   // cycle vectors
-    unsigned short* mask = nullptr;
     unsigned short* qmask = nullptr; // Q's box slots per next-level row (cycle restriction)
     unsigned char* jcnt = nullptr;   // |J_i| per continuing row
     float* feat = nullptr;           // collected first-pass features (rows x 24)
     float* slotw = nullptr;          // collected final slot weights (rows x 4)
     float* slotw0 = nullptr;         // collected first-pass slot weights (rows x 4)
     int* cnt = nullptr;
+    int* cnt2 = nullptr;             // entries per coarse row of T_{l+1} (grid levels)
     bool zero_into_e2 = false;       // first smoothing sweep target (fixed buffers)
     // levels without a grid (compatible relaxation)
     bool decided = false;            // coarsening fixed (on the first pass)
@@ -471,7 +473,7 @@ struct Engine : bamg_ctx {
     double* learn_acc = nullptr;
     int learn_grid = 0;
     // profiling
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_sweep, ev_gal, ev_ls, ev_gj, ev_gal_t, ev_gal_sym, ev_ls2;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_sweep, ev_gal, ev_ls, ev_gj, ev_gal_csr, ev_ls2;
     double gj_flops = 0;             // flops of the profiled dense updates
     // FGMRES: chain flags after each Arnoldi step, read by the host one step
     // late (pinned, two slots), the events that mark them, the inner
@@ -488,7 +490,7 @@ struct Engine : bamg_ctx {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cap_s) (void)hipStreamDestroy(cap_s);
-        for (auto* v : {&ev_sweep, &ev_gal, &ev_ls, &ev_gj, &ev_gal_t, &ev_gal_sym, &ev_ls2})
+        for (auto* v : {&ev_sweep, &ev_gal, &ev_ls, &ev_gj, &ev_gal_csr, &ev_ls2})
             for (auto& p : *v) { event_pool().put(p.first); event_pool().put(p.second); }
         A.release();
     }
@@ -625,6 +627,14 @@ struct Engine : bamg_ctx {
             lv.B.ci = A.alloc<int>(lv.B.cap);
             lv.B.v = A.alloc<T>(lv.B.cap);
         }
+        if (l > 0 && !unstructured) {
+            for (Csr<T>* M : {&lv.B, &lv.Tm}) {
+                M->gci = A.alloc<int>((size_t)n_l * 9);
+                M->gv = A.alloc<T>((size_t)n_l * 9);
+                M->cld = n_l;
+                if (ell9_on()) { M->cci = M->gci; M->cv = M->gv; }
+            }
+        }
         lv.dinv = A.alloc<T>(n_l);
         lv.U = A.alloc<T>((size_t)n_l * r);
         lv.V = A.alloc<T>((size_t)n_l * VS);
@@ -651,7 +661,7 @@ struct Engine : bamg_ctx {
         }
         lv.qc = A.alloc<int>((size_t)nc * 9);
         lv.qv = A.alloc<T>((size_t)nc * 9);
-        lv.mask = A.alloc<unsigned short>(nc);
+        lv.cnt2 = A.alloc<int>(nc + 1);
         lv.qmask = A.alloc<unsigned short>(nc);
         if (o.collect) {
             lv.feat = A.alloc<float>((size_t)lv.cont_rows * 24);
@@ -1065,54 +1075,51 @@ struct Engine : bamg_ctx {
         HIPCHK(hipGetLastError());
     }
 
+    // BAMG_SWEEP_ELL=0 in the environment: kernels read the coarse grid
+    // operators from CSR instead of their ELL-9 copies.
+    static bool ell9_on() {
+        const char* e = getenv("BAMG_SWEEP_ELL");
+        return !(e && e[0] == '0');
+    }
+
+    // Both Galerkin products of a grid level in one launch (ELL-9 output),
+    // then their CSR forms and the next level's D^-1.
     void galerkin(int l, bool profile) {
         auto& f = L[l];
         auto& c = L[l + 1];
         const int nc = c.rows;
         const int gb = ceil_div(nc, GAL_ROWS);
-        for (int which = 0; which < 2; ++which) {
-            Csr<T>& M = which == 0 ? f.B : f.Tm;
-            Csr<T>& Cm = which == 0 ? c.B : c.Tm;
-            // B_l's rows from its ELL copy (T_l's from CSR)
-            const EllSrc es = which == 0 ? ell_of(l) : EllSrc{nullptr, nullptr, 0, EF_CSR};
-            ef_dispatch(es.ef, [&](auto efc) {
-                constexpr int EF = decltype(efc)::value;
-                std::pair<hipEvent_t, hipEvent_t> ev;
-                if (profile && which == 0) ev = ev_begin();
-                LAUNCH(k_galerkin_symbolic<EF>, gb, GAL_THREADS, s, nc, (const ChainGeo*)c.dgeo, c.nch, f.qc, M.rp,
-                       M.ci, es.c, es.ld, f.pc, f.cnt, f.mask);
-                if (profile && which == 0) ev_end(ev, ev_gal_sym);
-                scan(nc, f.cnt, Cm.rp);
-                if (profile) ev = ev_begin();
-                LAUNCH((k_galerkin_numeric<T, EF>), gb, GAL_THREADS, s, nc, (const ChainGeo*)c.dgeo, c.nch, f.qc,
-                       (const T*)f.qv, M.rp, M.ci, (const T*)M.v, es.c, es.v, es.ld, f.pc, (const T*)f.pv, f.mask,
-                       Cm.rp, Cm.ci, Cm.v);
-                if (profile) ev_end(ev, which == 0 ? ev_gal : ev_gal_t);
-            });
-        }
+        // B_l's rows from its ELL copy; T_l's from its ELL-9 copy (T_0 = I)
+        const EllSrc eb = ell_of(l);
+        const EllSrc et = l == 0 ? EllSrc{nullptr, nullptr, 0, -1}
+                        : f.Tm.cci ? EllSrc{f.Tm.cci, f.Tm.cv, f.Tm.cld, EF_ELL9}
+                                   : EllSrc{nullptr, nullptr, 0, EF_CSR};
+        std::pair<hipEvent_t, hipEvent_t> ev;
+        if (profile) ev = ev_begin();
+        ef_dispatch(eb.ef, [&](auto efb) {
+            constexpr int EFB = decltype(efb)::value;
+            auto launch = [&](auto eft) {
+                constexpr int EFT = decltype(eft)::value;
+                LAUNCH((k_galerkin_bt<T, EFB, EFT>), gb, GAL_THREADS, s, nc, (const ChainGeo*)c.dgeo, c.nch, f.qc,
+                       (const T*)f.qv, (const int*)f.B.rp, (const int*)f.B.ci, (const T*)f.B.v, eb.c, eb.v, eb.ld,
+                       (const int*)f.Tm.rp, (const int*)f.Tm.ci, (const T*)f.Tm.v, et.c, et.v, et.ld, f.pc,
+                       (const T*)f.pv, c.B.gci, c.B.gv, f.cnt, c.Tm.gci, c.Tm.gv, f.cnt2);
+            };
+            if (et.ef < 0) launch(std::integral_constant<int, -1>{});
+            else if (et.ef == EF_ELL9) launch(std::integral_constant<int, EF_ELL9>{});
+            else launch(std::integral_constant<int, EF_CSR>{});
+        });
+        if (profile) ev_end(ev, ev_gal);
+        scan(nc, f.cnt, c.B.rp);
+        scan(nc, f.cnt2, c.Tm.rp);
+        if (profile) ev = ev_begin();
+        hipLaunchKernelGGL(k_ell9c_to_csr2<T>, dim3(nblk(nc), 2), dim3(BAMG_BLK), 0, s, nc, (const int*)c.B.gci,
+                           (const T*)c.B.gv, (const int*)c.B.rp, c.B.ci, c.B.v, (const int*)c.Tm.gci,
+                           (const T*)c.Tm.gv, (const int*)c.Tm.rp, c.Tm.ci, c.Tm.v);
+        HIPCHK(hipGetLastError());
+        if (profile) ev_end(ev, ev_gal_csr);
         zero(err, sizeof(int) * 4);
         LAUNCH(k_dinv<T>, nblk(nc), BAMG_BLK, s, nc, c.B.rp, c.B.ci, c.B.v, o.omega, c.dinv, err);
-        build_ell9(l + 1);
-    }
-
-    // Column-major ELL-9 copy of B_l on a grid level below the finest (every
-    // coarse row lies in the 3 x 3 box), for the cycle's sweeps and residual
-    // (BAMG_SWEEP_ELL=0 turns it off).  Rebuilt with every Galerkin product.
-    void build_ell9(int l) {
-        const char* e = getenv("BAMG_SWEEP_ELL");
-        if (e && e[0] == '0') return;
-        auto& lv = L[l];
-        const int rows = lv.rows;
-        if (!lv.B.cci) {
-            lv.B.cci = A.alloc<int>((size_t)rows * 9);
-            lv.B.cv = A.alloc<T>((size_t)rows * 9);
-            invalidate_graph();
-        }
-        // a row above 9 entries cannot come out of the box-masked product; the
-        // flag is read with the other deferred checks at the end of the setup
-        LAUNCH((k_csr_to_ell9c<T>), nblk(rows), BAMG_BLK, s, rows, (const int*)lv.B.rp, (const int*)lv.B.ci,
-               (const T*)lv.B.v, lv.B.cci, lv.B.cv, derr);
-        lv.B.cld = rows;
     }
 
     void build_level(int l, int use_v, bool inject, bool profile) {
@@ -1806,8 +1813,7 @@ struct Engine : bamg_ctx {
             st.mlp_fallback = (int64_t)la[1];
         }
         acc(ev_gal, st.galerkin_ms, st.galerkin_launches);
-        acc(ev_gal_t, st.gal_t_ms, st.gal_t_launches);
-        acc(ev_gal_sym, st.gal_sym_ms, st.gal_sym_launches);
+        acc(ev_gal_csr, st.gal_csr_ms, st.gal_csr_launches);
         acc(ev_ls, st.lsfit_ms, st.lsfit_launches);
         acc(ev_ls2, st.lsfit2_ms, st.lsfit2_launches);
         acc(ev_gj, st.dense_update_ms, st.dense_update_launches);
@@ -1826,16 +1832,15 @@ struct Engine : bamg_ctx {
         if (L.size() > 1 && !unstructured) {
             // every array once (neighbour re-reads served from cache): Q
             // (ELL-9 columns and values), B_0's rows (ELL-4 copy or CSR),
-            // P (ELL-4), the box masks and row pointers of the product, and
-            // the product's stored entries
+            // P (ELL-4); written: both products' ELL-9 arrays and row
+            // counts.  The CSR step reads the row pointers and the stored
+            // entries of both ELL-9 copies and writes them as CSR.
             const long long nc = L[1].rows, nnzb1 = g[1];
             const long long nnzt1 = t1 ? g[nl + 1] : 0;
-            const long long q = nc * 9 * (4 + vb), pb = n0 * 4 * (4 + vb), ctl = nc * 2 + (nc + 1) * 4;
+            const long long q = nc * 9 * (4 + vb), pb = n0 * 4 * (4 + vb);
             const long long brows = L[0].B.eci ? 4LL * n0 * (4 + vb) : (n0 + 1) * 4 + (long long)nnz0 * (4 + vb);
-            const long long bcols = L[0].B.eci ? 4LL * n0 * 4 : (n0 + 1) * 4 + (long long)nnz0 * 4;
-            st.galerkin_bytes = q + brows + pb + ctl + nnzb1 * (4 + vb);
-            st.gal_t_bytes = q + pb + ctl + nnzt1 * (4 + vb);
-            st.gal_sym_bytes = nc * 9 * 4 + bcols + n0 * 4 * 4 + nc * 4 + nc * 2;
+            st.galerkin_bytes = q + brows + pb + 2 * nc * 9 * (4 + vb) + 2 * nc * 4;
+            st.gal_csr_bytes = 2 * (nc + 1) * 4 + 2 * (nnzb1 + nnzt1) * (4 + vb);
             // the fit reads the test vectors, writes P (ELL-4) and |J_i|;
             // the first pass also injects U on the coarse points
             st.lsfit_bytes = n0 * (long long)r * vb + pb + n0 + nc * (long long)r * vb;

@@ -293,24 +293,11 @@ k_spmv(int n, const int* __restrict__ rp, const int* __restrict__ ci, const M* _
     y[i] = alpha * acc;
 }
 
-// Column-major ELL-9 copy of a coarse operator (entry k of row i at k ld + i,
-// ld = the level's row count; the kernels below may run over a row prefix n;
-// CSR order, padded with (i, 0)): the one-row-per-thread cycle kernels load
-// the 9 columns and values of their rows with coalesced, independent loads.
-// err = 1 when a row has more than 9 entries.
-template <typename M>
-__global__ void k_csr_to_ell9c(int n, const int* __restrict__ rp, const int* __restrict__ ci, const M* __restrict__ v,
-                               int* __restrict__ cci, M* __restrict__ cv, int* __restrict__ err) {
-    const int i = blockIdx.x * BAMG_BLK + threadIdx.x;
-    if (i >= n) return;
-    const int p0 = rp[i], len = rp[i + 1] - p0;
-    if (len > 9) { *err = 1; return; }
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        cci[(size_t)k * n + i] = k < len ? ci[p0 + k] : i;
-        cv[(size_t)k * n + i] = k < len ? v[p0 + k] : (M)0;
-    }
-}
+// Coarse grid operators also live in a column-major ELL-9 form (entry k of
+// row i at k ld + i, ld = the level's row count; the kernels below may run
+// over a row prefix n; CSR order, padded with (i, 0)), which the Galerkin
+// product writes directly: the one-row-per-thread cycle kernels load the 9
+// columns and values of their rows with coalesced, independent loads.
 
 // Both ELL-4 copies of the finest B in the mixed form from its FP64 CSR in
 // one pass: the shared column array, the FP64 values and their FP32
@@ -1230,84 +1217,58 @@ __device__ __forceinline__ unsigned gal_slot(int coff, int Ia, int Ib, int i, co
     return mask;
 }
 
-// Symbolic pass of Q (M P): 9-bit mask of the coarse box slots reached by row
-// I (every coarse stencil lies in that box: Q, M and P each reach one grid
-// step).  cnt[I] = number of distinct columns.  M == identity when mrp is null.
-template <int EF>
+// Both products of a grid level in one pass: B_{l+1} = Q (B_l P) and
+// T_{l+1} = Q (T_l P) (Algorithm 3), nine threads per coarse row I (GAL_ROWS
+// rows per block), thread (I, s) taking slot s of Q row I (fine point
+// i = qc[9I + s]) for both products, so Q and P are read once.  B_l's rows
+// come from the storage EFB names, T_l's from EFT (EFT < 0: T_l = I).  The
+// sums are those of the separate numeric pass: q_Is (sum_j m_ij p_jJ) in
+// row-entry and then P-slot order, the nine slots added in order s = 0..8.
+// The pattern is the symbolic one (the box slots reached by any product of
+// stored entries, structural zeros kept).  Thread u writes box slot u of row
+// I at its rank among the row's structural slots (ascending column) into the
+// column-major ELL-9 arrays of each product (slot k of row I at k nc + I),
+// the free slots padded with (I, 0); *cnt[I] = structural slots of the row.
+template <typename MV, int EFB, int EFT>
 __global__ void __launch_bounds__(GAL_THREADS)
-k_galerkin_symbolic(int nc, const ChainGeo* __restrict__ geoc, int nch,
-                    const int* __restrict__ qc, const int* __restrict__ mrp,
-                    const int* __restrict__ mci, const int* __restrict__ eci, int eld, const int* __restrict__ pc,
-                    int* __restrict__ cnt, unsigned short* __restrict__ mask_out) {
+k_galerkin_bt(int nc, const ChainGeo* __restrict__ geoc, int nch, const int* __restrict__ qc,
+              const MV* __restrict__ qv, const int* __restrict__ brp, const int* __restrict__ bci,
+              const MV* __restrict__ bv, const int* __restrict__ beci, const MV* __restrict__ bev, int beld,
+              const int* __restrict__ trp, const int* __restrict__ tci, const MV* __restrict__ tv,
+              const int* __restrict__ teci, const MV* __restrict__ tev, int teld, const int* __restrict__ pc,
+              const MV* __restrict__ pv, int* __restrict__ bcc, MV* __restrict__ bcv, int* __restrict__ bcnt,
+              int* __restrict__ tcc, MV* __restrict__ tcv, int* __restrict__ tcnt) {
+    __shared__ MV sv[GAL_THREADS][9];
     __shared__ unsigned sm[GAL_THREADS];
     const int lr = threadIdx.x / 9, s = threadIdx.x % 9;
     const int I = xcd_tile(blockIdx.x, gridDim.x) * GAL_ROWS + lr;
-    unsigned mask = 0;
-    if (I < nc) {
-        int i = qc[(size_t)I * 9 + s];
-        if (i >= 0) {
-            const ChainGeo g = geoc[find_chain(geoc, nch, I)];
-            const int lI = I - g.off;
-            int Ia = (int)g.dy.div((uint32_t)lI), Ib = lI - Ia * g.ny;
-            mask = gal_slot<float, false, EF>(g.off, Ia, Ib, i, g.dy, g.nx, g.ny, g.periodic, mrp, mci,
-                                              (const float*)nullptr, eci, (const float*)nullptr, eld, pc,
-                                              (const float*)nullptr, nullptr);
-        }
-    }
-    sm[threadIdx.x] = mask;
-    __syncthreads();
-    if (s == 0 && I < nc) {
-        unsigned m = 0;
-        for (int u = 0; u < 9; ++u) m |= sm[threadIdx.x + u];
-        // columns of distinct slots are distinct (coarse sides >= 3)
-        cnt[I] = __popc(m);
-        mask_out[I] = (unsigned short)m;
-    }
-}
-
-// Numeric pass: row I of Q (M P) = sum_s q_Is (sum_j m_ij p_jJ) with the Q
-// slots added in order s = 0..8 (fixed order), written in ascending coarse
-// column at crp[I].
-template <typename MV, int EF>
-__global__ void __launch_bounds__(GAL_THREADS)
-k_galerkin_numeric(int nc, const ChainGeo* __restrict__ geoc, int nch,
-                   const int* __restrict__ qc, const MV* __restrict__ qv,
-                   const int* __restrict__ mrp, const int* __restrict__ mci, const MV* __restrict__ mv,
-                   const int* __restrict__ eci, const MV* __restrict__ ev, int eld,
-                   const int* __restrict__ pc, const MV* __restrict__ pv,
-                   const unsigned short* __restrict__ mask_in, const int* __restrict__ crp,
-                   int* __restrict__ cci, MV* __restrict__ cv) {
-    __shared__ MV sv[GAL_THREADS][9];
-    const int lr = threadIdx.x / 9, s = threadIdx.x % 9;
-    const int I = xcd_tile(blockIdx.x, gridDim.x) * GAL_ROWS + lr;
-    MV tmp[9];
+    MV tb[9], tt[9];
 #pragma unroll
-    for (int u = 0; u < 9; ++u) tmp[u] = 0;
+    for (int u = 0; u < 9; ++u) { tb[u] = 0; tt[u] = 0; }
+    unsigned mb = 0, mt = 0;
     int Ia = 0, Ib = 0, ncx = 1, ncy = 1, periodic = 0, goff = 0;
     if (I < nc) {
         const ChainGeo g = geoc[find_chain(geoc, nch, I)];
         ncx = g.nx; ncy = g.ny; periodic = g.periodic; goff = g.off;
         const int lI = I - g.off;
         Ia = (int)g.dy.div((uint32_t)lI); Ib = lI - Ia * ncy;
-        int i = qc[(size_t)I * 9 + s];
+        const int i = qc[(size_t)I * 9 + s];
         if (i >= 0) {
-            MV q = qv[(size_t)I * 9 + s];
-            gal_slot<MV, true, EF>(g.off, Ia, Ib, i, g.dy, ncx, ncy, periodic, mrp, mci, mv, eci, ev, eld, pc, pv,
-                                   tmp);
+            const MV q = qv[(size_t)I * 9 + s];
+            mb = gal_slot<MV, true, EFB>(g.off, Ia, Ib, i, g.dy, ncx, ncy, periodic, brp, bci, bv, beci, bev, beld,
+                                         pc, pv, tb);
+            if constexpr (EFT < 0)
+                mt = gal_slot<MV, true, EF_CSR>(g.off, Ia, Ib, i, g.dy, ncx, ncy, periodic, (const int*)nullptr,
+                                                (const int*)nullptr, (const MV*)nullptr, (const int*)nullptr,
+                                                (const MV*)nullptr, 0, pc, pv, tt);
+            else
+                mt = gal_slot<MV, true, EFT>(g.off, Ia, Ib, i, g.dy, ncx, ncy, periodic, trp, tci, tv, teci, tev,
+                                             teld, pc, pv, tt);
 #pragma unroll
-            for (int u = 0; u < 9; ++u) tmp[u] = q * tmp[u];
+            for (int u = 0; u < 9; ++u) { tb[u] = q * tb[u]; tt[u] = q * tt[u]; }
         }
     }
-#pragma unroll
-    for (int u = 0; u < 9; ++u) sv[threadIdx.x][u] = tmp[u];
-    __syncthreads();
-    if (I >= nc) return;
-    // thread (I, s) finalises box slot u = s of row I
-    const int u = s;
-    unsigned mask = mask_in[I];
-    if (!((mask >> u) & 1)) return;
-    MV acc = 0;
-    for (int t = 0; t < 9; ++t) acc += sv[lr * 9 + t][u];
+    // the row's coarse columns of the nine box slots
     int col[9];
 #pragma unroll
     for (int w = 0; w < 9; ++w) {
@@ -1318,11 +1279,53 @@ k_galerkin_numeric(int nc, const ChainGeo* __restrict__ geoc, int nch,
         }
         col[w] = goff + a * ncy + b;
     }
-    int rank = 0;
+    for (int prod = 0; prod < 2; ++prod) {
+        if (prod) __syncthreads();
 #pragma unroll
-    for (int t = 0; t < 9; ++t) rank += ((mask >> t) & 1) && (col[t] < col[u]);
-    cci[crp[I] + rank] = col[u];
-    cv[crp[I] + rank] = acc;
+        for (int u = 0; u < 9; ++u) sv[threadIdx.x][u] = prod ? tt[u] : tb[u];
+        sm[threadIdx.x] = prod ? mt : mb;
+        __syncthreads();
+        if (I < nc) {
+            int* cc = prod ? tcc : bcc;
+            MV* cv = prod ? tcv : bcv;
+            unsigned mask = 0;
+            for (int t = 0; t < 9; ++t) mask |= sm[lr * 9 + t];
+            const int u = s;
+            const int cnt = __popc(mask);
+            if ((mask >> u) & 1) {
+                MV acc = 0;
+                for (int t = 0; t < 9; ++t) acc += sv[lr * 9 + t][u];
+                int rank = 0;
+#pragma unroll
+                for (int t = 0; t < 9; ++t) rank += ((mask >> t) & 1) && (col[t] < col[u]);
+                cc[(size_t)rank * nc + I] = col[u];
+                cv[(size_t)rank * nc + I] = acc;
+            }
+            if (u >= cnt) { cc[(size_t)u * nc + I] = I; cv[(size_t)u * nc + I] = (MV)0; }
+            if (u == 0) (prod ? tcnt : bcnt)[I] = cnt;
+        }
+    }
+}
+
+// CSR rows of both products from their ELL-9 copies (blockIdx.y: 0 = B,
+// 1 = T): row I's first rp[I + 1] - rp[I] slots, in order.
+template <typename MV>
+__global__ void k_ell9c_to_csr2(int nc, const int* __restrict__ bcc, const MV* __restrict__ bcv,
+                                const int* __restrict__ brp, int* __restrict__ bci, MV* __restrict__ bv,
+                                const int* __restrict__ tcc, const MV* __restrict__ tcv, const int* __restrict__ trp,
+                                int* __restrict__ tci, MV* __restrict__ tv) {
+    const int I = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    if (I >= nc) return;
+    const bool tt = blockIdx.y == 1;
+    const int* cc = tt ? tcc : bcc;
+    const MV* cv = tt ? tcv : bcv;
+    const int* rp = tt ? trp : brp;
+    int* ci = tt ? tci : bci;
+    MV* v = tt ? tv : bv;
+    const int p0 = rp[I], len = rp[I + 1] - p0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+        if (k < len) { ci[p0 + k] = cc[(size_t)k * nc + I]; v[p0 + k] = cv[(size_t)k * nc + I]; }
 }
 
 // ---------------------------------------------------------------- up-leg
