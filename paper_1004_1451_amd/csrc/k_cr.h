@@ -260,7 +260,7 @@ k_ls_fit_u(int n, int Ru, int Rv, int VS, const T* __restrict__ U, const T* __re
     int jl[4] = {0, 0, 0, 0};
     int nsel = 0;
     double detJ = 1.0;
-    double G4[4][4], b4[4], L[4][4], z[4];
+    double G4[4][4], b4[4], L[4][4], il[4], z[4];
     auto load_set = [&](const int (&idx)[4], int m) {
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
@@ -292,7 +292,7 @@ k_ls_fit_u(int n, int Ru, int Rv, int VS, const T* __restrict__ U, const T* __re
             if (!put && m < 4) idx[m++] = c;
             load_set(idx, m);
             double det;
-            const bool ok = chol4(G4, b4, (1 << m) - 1, L, z, det);
+            const bool ok = chol4(G4, b4, (1 << m) - 1, L, il, z, det);
             const double gcc = sG[lsu_gi(c, c)][tid];
             if (!ok || !(det > 1e-10 * gcc * detJ)) continue;
             double Lv = sigma;
@@ -308,7 +308,7 @@ k_ls_fit_u(int n, int Ru, int Rv, int VS, const T* __restrict__ U, const T* __re
         ++nsel;
         load_set(jl, nsel);
         double det;
-        chol4(G4, b4, (1 << nsel) - 1, L, z, det);
+        chol4(G4, b4, (1 << nsel) - 1, L, il, z, det);
         detJ = det;
     }
     double p[4] = {0.0, 0.0, 0.0, 0.0};
@@ -319,7 +319,7 @@ k_ls_fit_u(int n, int Ru, int Rv, int VS, const T* __restrict__ U, const T* __re
     } else {
         load_set(jl, nsel);
         double det;
-        chol4(G4, b4, (1 << nsel) - 1, L, z, det);
+        chol4(G4, b4, (1 << nsel) - 1, L, il, z, det);
 #pragma unroll
         for (int a = 3; a >= 0; --a) {
             if (a >= nsel) continue;
@@ -327,7 +327,7 @@ k_ls_fit_u(int n, int Ru, int Rv, int VS, const T* __restrict__ U, const T* __re
 #pragma unroll
             for (int c = a + 1; c < 4; ++c)
                 if (c < nsel) s -= L[c][a] * p[c];
-            p[a] = s / L[a][a];
+            p[a] = s * il[a];
         }
     }
     // the slots are in ascending coarse index, so the row is already sorted

@@ -751,16 +751,19 @@ __global__ void k_colnorm_final(const ChainGeo* __restrict__ geo, int seg_rows, 
 
 // ---------------------------------------------------------------- LS fit
 // Masked Cholesky of the 4x4 Gram G on the slot set S (bit mask), slot order.
-// Fills lower factor L (entries outside S untouched / zero) and returns false
-// if a pivot is not positive.  z = L^-1 b on S; log-free determinant product.
+// Fills lower factor L (entries outside S untouched / zero), the reciprocals
+// il of its diagonal, z = L^-1 b on S and the determinant product, and
+// returns false if a pivot is not positive.  Divisions by a pivot are
+// products with its reciprocal (v_rcp_f64 refined by two Newton steps).
 __device__ __forceinline__ bool chol4(const double G[4][4], const double b[4], int S, double L[4][4],
-                                      double z[4], double& det) {
+                                      double il[4], double z[4], double& det) {
     det = 1.0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) L[i][j] = 0.0;
         z[i] = 0.0;
+        il[i] = 0.0;
     }
     bool ok = true;
 #pragma unroll
@@ -771,19 +774,20 @@ __device__ __forceinline__ bool chol4(const double G[4][4], const double b[4], i
         for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
         if (!(d > 0.0)) { ok = false; d = 1.0; }
         det *= d;
-        double lj = sqrt(d);
+        const double lj = sqrt(d), r = cz_recip(lj);
         L[j][j] = lj;
+        il[j] = r;
         double zz = b[j];
 #pragma unroll
         for (int k = 0; k < j; ++k) zz -= L[j][k] * z[k];
-        z[j] = zz / lj;
+        z[j] = zz * r;
 #pragma unroll
         for (int i = j + 1; i < 4; ++i) {
             if (!((S >> i) & 1)) continue;
             double s = G[i][j];
 #pragma unroll
             for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
-            L[i][j] = s / lj;
+            L[i][j] = s * r;
         }
     }
     return ok;
@@ -911,21 +915,21 @@ __device__ __forceinline__ void ls_point(int i, const ChainGeo& g, int ia, int i
     // set with a factor 100 over the admissibility bound, so rounding cannot
     // pass a slot the greedy steps would reject; the slots are a prefix.
     int J = 0, nsel = 0;
-    double L[4][4], z[4], detJ = 1.0;
+    double L[4][4], il[4], z[4], detJ = 1.0;
     bool all = ns > 0 && ns <= caliber;
     if (all) {
         double det;
-        all = chol4(P.G, P.b, valid, L, z, det);
+        all = chol4(P.G, P.b, valid, L, il, z, det);
         double W[4][4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            W[j][j] = j < ns ? 1.0 / L[j][j] : 0.0;
+            W[j][j] = j < ns ? il[j] : 0.0;
 #pragma unroll
             for (int i = j + 1; i < 4; ++i) {
                 double t = 0.0;
 #pragma unroll
                 for (int k = j; k < i; ++k) t += L[i][k] * W[k][j];
-                W[i][j] = i < ns ? -t / L[i][i] : 0.0;
+                W[i][j] = i < ns ? -t * il[i] : 0.0;
             }
         }
 #pragma unroll
@@ -934,10 +938,13 @@ __device__ __forceinline__ void ls_point(int i, const ChainGeo& g, int ia, int i
             double gi = 0.0;
 #pragma unroll
             for (int k = g; k < 4; ++k) gi += W[k][g] * W[k][g];
-            all = all && (1.0 / gi > 1e-8 * P.G[g][g]);
+            // the pivot 1 / gi of slot g against all the others must pass
+            // 100 times the admissibility bound
+            all = all && (1.0 > 1e-8 * P.G[g][g] * gi);
         }
     }
     if (all) { J = valid; nsel = ns; }
+    bool fresh = all;        // L, il, z hold the factor of G_JJ
 #pragma unroll
     for (int step = 0; step < 4; ++step) {
         if (all || nsel >= caliber) break;
@@ -948,7 +955,8 @@ __device__ __forceinline__ void ls_point(int i, const ChainGeo& g, int ia, int i
             if (!((valid >> c) & 1) || ((J >> c) & 1)) continue;
             int S = J | (1 << c);
             double det;
-            bool ok = chol4(P.G, P.b, S, L, z, det);
+            fresh = false;
+            bool ok = chol4(P.G, P.b, S, L, il, z, det);
             if (!ok || !(det > 1e-10 * P.G[c][c] * detJ)) continue;
             double Lv = sigma;
 #pragma unroll
@@ -959,8 +967,9 @@ __device__ __forceinline__ void ls_point(int i, const ChainGeo& g, int ia, int i
         J |= 1 << best;
         ++nsel;
         double det;
-        chol4(P.G, P.b, J, L, z, det);
+        chol4(P.G, P.b, J, L, il, z, det);
         detJ = det;
+        fresh = true;
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s) P.p[s] = 0.0;
@@ -969,8 +978,12 @@ __device__ __forceinline__ void ls_point(int i, const ChainGeo& g, int ia, int i
         P.p[0] = 1.0;
         P.Lls = sigma - 2.0 * P.b[0] + P.G[0][0];
     } else {
-        double det;
-        chol4(P.G, P.b, J, L, z, det);
+        // the factor of G_JJ is still in L, il, z unless candidates were
+        // tried after the last selection
+        if (!fresh) {
+            double det;
+            chol4(P.G, P.b, J, L, il, z, det);
+        }
         double Lv = sigma;
 #pragma unroll
         for (int s = 0; s < 4; ++s) Lv -= z[s] * z[s];
@@ -982,7 +995,7 @@ __device__ __forceinline__ void ls_point(int i, const ChainGeo& g, int ia, int i
             double s = z[j];
 #pragma unroll
             for (int k = j + 1; k < 4; ++k) s -= L[k][j] * P.p[k];
-            P.p[j] = s / L[j][j];
+            P.p[j] = s * il[j];
         }
     }
     P.J = J;
@@ -1308,24 +1321,47 @@ k_galerkin_bt(int nc, const ChainGeo* __restrict__ geoc, int nch, const int* __r
 }
 
 // CSR rows of both products from their ELL-9 copies (blockIdx.y: 0 = B,
-// 1 = T): row I's first rp[I + 1] - rp[I] slots, in order.
+// 1 = T): row I's first rp[I + 1] - rp[I] slots, in order.  A workgroup
+// takes BAMG_BLK consecutive rows: it reads their nine slots column by
+// column (coalesced) into LDS, then writes the rows' contiguous CSR range
+// entry by entry (coalesced), each entry finding its row by binary search
+// over the rows' pointers in LDS.
 template <typename MV>
-__global__ void k_ell9c_to_csr2(int nc, const int* __restrict__ bcc, const MV* __restrict__ bcv,
-                                const int* __restrict__ brp, int* __restrict__ bci, MV* __restrict__ bv,
-                                const int* __restrict__ tcc, const MV* __restrict__ tcv, const int* __restrict__ trp,
-                                int* __restrict__ tci, MV* __restrict__ tv) {
-    const int I = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
-    if (I >= nc) return;
+__global__ void __launch_bounds__(BAMG_BLK)
+k_ell9c_to_csr2(int nc, const int* __restrict__ bcc, const MV* __restrict__ bcv, const int* __restrict__ brp,
+                int* __restrict__ bci, MV* __restrict__ bv, const int* __restrict__ tcc, const MV* __restrict__ tcv,
+                const int* __restrict__ trp, int* __restrict__ tci, MV* __restrict__ tv) {
+    __shared__ int sc[9][BAMG_BLK];
+    __shared__ MV sv[9][BAMG_BLK];
+    __shared__ int sp[BAMG_BLK + 1];
     const bool tt = blockIdx.y == 1;
     const int* cc = tt ? tcc : bcc;
     const MV* cv = tt ? tcv : bcv;
     const int* rp = tt ? trp : brp;
     int* ci = tt ? tci : bci;
     MV* v = tt ? tv : bv;
-    const int p0 = rp[I], len = rp[I + 1] - p0;
+    const int I0 = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK;
+    const int rows = min(BAMG_BLK, nc - I0);
+    const int t = threadIdx.x;
+    if (t < rows) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k)
-        if (k < len) { ci[p0 + k] = cc[(size_t)k * nc + I]; v[p0 + k] = cv[(size_t)k * nc + I]; }
+        for (int k = 0; k < 9; ++k) { sc[k][t] = cc[(size_t)k * nc + I0 + t]; sv[k][t] = cv[(size_t)k * nc + I0 + t]; }
+    }
+    if (t < rows) sp[t] = rp[I0 + t];
+    if (t == 0) sp[rows] = rp[I0 + rows];
+    __syncthreads();
+    const int base = sp[0], len = sp[rows] - base;
+    for (int e = t; e < len; e += BAMG_BLK) {
+        const int pe = base + e;
+        int lo = 0, hi = rows - 1;          // the row r with sp[r] <= pe < sp[r + 1]
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sp[mid] <= pe) lo = mid; else hi = mid - 1;
+        }
+        const int k = pe - sp[lo];
+        ci[pe] = sc[k][lo];
+        v[pe] = sv[k][lo];
+    }
 }
 
 // ---------------------------------------------------------------- up-leg
