@@ -303,6 +303,8 @@ def main():
                     help="tandem workload: FGMRES (Section 4.2), preconditioned Arnoldi (Section 4.3) or the "
                          "stand-alone MLE iteration (Section 4.1)")
     ap.add_argument("--mu", type=int, choices=[1, 2], default=1, help="setup cycle index (1 = V, 2 = W)")
+    ap.add_argument("--caliber", type=int, default=4,
+                    help="most coarse points an F point interpolates from (Algorithm 2; the paper's tables use 2)")
     ap.add_argument("--relax", choices=["jacobi", "mcgs"], default="jacobi",
                     help="tandem workload: omega-Jacobi (the paper's) or multicolour Gauss-Seidel sweeps")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -346,7 +348,8 @@ def main():
         rp, ci, v = B.device_csr(ch)
         x = torch.empty(ch.n, dtype=torch.float64, device="cuda")
         relax = B.RELAX_MCGS if args.relax == "mcgs" else B.RELAX_JACOBI
-        opts = B.default_options(levels=args.levels, precision=prec, profile=1, relax=relax, mu=args.mu)
+        opts = B.default_options(levels=args.levels, precision=prec, profile=1, relax=relax, mu=args.mu,
+                                 caliber=args.caliber)
 
         def step():
             h = B.Hierarchy(ch.n, rp, ci, v, (ch.nx, ch.ny, int(ch.periodic)), args.r, opts)
@@ -377,7 +380,8 @@ def main():
             # outside the timed region: the plain FP64 form, its time per step
             # and how far the mixed solution is from it
             x_mixed = x.clone()
-            opts = B.default_options(levels=args.levels, precision=B.FP64, profile=1, relax=relax, mu=args.mu)
+            opts = B.default_options(levels=args.levels, precision=B.FP64, profile=1, relax=relax, mu=args.mu,
+                                     caliber=args.caliber)
             sec64, res64 = _timed(step, argparse.Namespace(warmup=1, steps=max(1, min(args.steps, 3))))
             detail["fp64_ms_per_step"] = round(sec64 * 1e3, 3)
             detail["fp64_cycles"] = res64[-1][0].cycles
@@ -397,7 +401,8 @@ def main():
                        **({"relax": "multicolour Gauss-Seidel"} if args.relax == "mcgs" else {}),
                        **({"solver": {"parnoldi": "preconditioned Arnoldi", "mle": "MLE iteration"}[args.solver]}
                           if args.solver != "fgmres" else {}),
-                       **({"setup_cycle": "W"} if args.mu == 2 else {})},
+                       **({"setup_cycle": "W"} if args.mu == 2 else {}),
+                       **({"caliber": args.caliber} if args.caliber != 4 else {})},
             "roofline": roof, "detail": detail,
         }
         if not args.no_cpu_baseline:
@@ -471,8 +476,9 @@ def main():
     elif args.workload == "learned":
         from paper_1004_1451_amd import learned as LRN
         t0 = time.perf_counter()
-        train = C.training_chains(args.train_chains)
-        params, tinfo, sizes = LRN.train(train, r=args.r, levels=args.levels, n_val=4, epochs=args.epochs)
+        # the library builds the training chains, collects the pairs and trains
+        params, tinfo = LRN.train(n_chains=args.train_chains, n_val=4, r=args.r, levels=args.levels,
+                                  epochs=args.epochs)
         train_s = time.perf_counter() - t0
         ch = C.tandem_queue(args.N)
         rp, ci, v = B.device_csr(ch)
@@ -516,7 +522,7 @@ def main():
                                    f"tol {args.tol:g}; network trained on {args.train_chains} jittered tandems "
                                    f"N in [255,1023]", "precision": "mixed+learned"},
             "roofline": roof,
-            "detail": {"forms": res, "train_s": round(train_s, 2), "train_points": sizes[0], "val_points": sizes[1],
+            "detail": {"forms": res, "train_s": round(train_s, 2),
                        "train_steps": tinfo.steps, "train_ms": round(tinfo.ms, 1),
                        "val_loss_first": tinfo.val_loss_first, "val_loss_last": tinfo.val_loss_last,
                        "learned_vs_plain_fp64": round(res["plain_fp64"]["ms_per_step"] /

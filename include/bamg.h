@@ -156,6 +156,8 @@ typedef struct {
     int32_t cr_rounds;   /* at most this many CR relaxations per level (64)    */
     int32_t nbr_dist;    /* z of eq. neighbor_def: path length of the candidate
                             sets N_i (only 1 is built)                        */
+    const char* mlp_weights_path; /* learned form: network file written by
+                            bamg_mlp_train_spec, read when mlp_weights is NULL */
 } bamg_options;
 
 typedef struct {
@@ -411,6 +413,47 @@ int bamg_mlp_loss_grad(const float* feat, const float* tgt, int64_t n, const flo
    opt and info are host structs (opt NULL = defaults; info may be NULL). */
 int bamg_mlp_train(const float* feat, const float* tgt, int64_t n, const float* vfeat, const float* vtgt, int64_t nv,
                    float* params, const bamg_mlp_train_opts* opt, bamg_mlp_train_info* info, void* stream);
+
+/* Training pairs of the learned form from a handle set up with
+   options.collect (least-squares form): for every F point of every
+   non-coarsest level, its 24 first-pass features (feat, n x 24) and, as the
+   target, the correction of its fitted slot weights, final minus first-pass
+   (tgt, n x 4), in level order.  Only ordinary points are kept: at least one
+   valid slot, every feature within +-16 and every correction within +-1.
+   feat and tgt are device arrays of cap rows, or both NULL to count only;
+   *count (host) = the pairs.  BAMG_EINVAL if they exceed cap (*count still
+   set).  Synchronises the handle's stream. */
+int bamg_mlp_collect(bamg_handle h, float* feat, float* tgt, int64_t cap, int64_t* count);
+
+/* The training set of the learned form, built by the library itself: n_chains
+   jittered tandem queues (Section 5, Table 2 rates 11/31, 10/31, 10/31, each
+   times 1 + jitter (2u - 1)), chain c of side side_min + floor((side_max -
+   side_min + 1) u_c), u_c from the counter generator (seed, stream 8, c),
+   rates from (seed, stream 3, 3 (1000 + c) + k); each set up in FP64 with
+   r test vectors and `levels` levels, its pairs collected as by
+   bamg_mlp_collect; the last n_val chains validate. */
+typedef struct {
+    int32_t n_chains;    /* training and validation chains (32)                */
+    int32_t n_val;       /* of which the last n_val validate (4)               */
+    int32_t side_min, side_max; /* grid sides N + 1 (256, 1024)                */
+    double jitter;       /* relative rate jitter (0.2)                          */
+    uint64_t seed;       /* chain sides and rates (0)                           */
+    int32_t r, levels;   /* setups that collect the pairs (12, 6)               */
+    uint64_t init_seed;  /* He-uniform initial weights (5)                      */
+    bamg_mlp_train_opts train; /* Adam (8 epochs, batch 4096, lr 1e-3, seed 6) */
+} bamg_train_spec;
+
+/* Fills *spec with the defaults above. */
+void bamg_train_spec_default(bamg_train_spec* spec);
+
+/* Builds the training set of *spec, initialises a network (bamg_mlp_init
+   with init_seed) and trains it (bamg_mlp_train with spec->train).  The
+   parameters go to params (device, BAMG_MLP_NPARAM floats) when not NULL and
+   to the file out_path when not NULL ("BAMGMLP1", int32 count, FP32 values;
+   options.mlp_weights_path reads it); info (host) may be NULL.  Allocates
+   and frees its own device memory; synchronises the stream. */
+int bamg_mlp_train_spec(const bamg_train_spec* spec, const char* out_path, float* params,
+                        bamg_mlp_train_info* info, void* stream);
 
 /* nu omega-Jacobi sweeps X <- X + omega D^-1 (F - B X) on caller data
    (Section 3, eq. amg_relax): B = I - A from device CSR of A (as in

@@ -35,7 +35,8 @@ ERROR_NAMES = {EINVAL: "EINVAL", ENOTSTOCH: "ENOTSTOCH", EZERODIAG: "EZERODIAG",
 EXPORTS = ["bamg_options_default", "bamg_setup", "bamg_solve", "bamg_free", "bamg_last_error", "bamg_get_stats",
            "bamg_level_info_get", "bamg_export", "bamg_apply_vcycle", "bamg_relax", "bamg_setup_batched",
            "bamg_solve_batched", "bamg_trim", "bamg_mlp_init", "bamg_mlp_forward", "bamg_mlp_loss_grad",
-           "bamg_mlp_train", "bamg_mle_iterate", "bamg_mlp_forward_noalloc"]
+           "bamg_mlp_train", "bamg_mle_iterate", "bamg_mlp_forward_noalloc", "bamg_mlp_collect",
+           "bamg_train_spec_default", "bamg_mlp_train_spec"]
 
 
 class BamgError(RuntimeError):
@@ -58,7 +59,7 @@ class Options(C.Structure):
                 ("setup_passes", C.c_int32), ("collect", C.c_int32), ("mlp_judge", C.c_float),
                 ("relax", C.c_int32), ("gs_omega", C.c_double), ("mu", C.c_int32),
                 ("cr_theta", C.c_double), ("cr_nu", C.c_int32), ("cr_rounds", C.c_int32),
-                ("nbr_dist", C.c_int32)]
+                ("nbr_dist", C.c_int32), ("mlp_weights_path", C.c_char_p)]
 
 
 class SolveInfo(C.Structure):
@@ -91,6 +92,12 @@ class MlpTrainInfo(C.Structure):
     _fields_ = [("steps", C.c_int32), ("train_loss_first", C.c_double), ("train_loss_last", C.c_double),
                 ("val_loss_first", C.c_double), ("val_loss_last", C.c_double), ("ms", C.c_double),
                 ("val_len", C.c_int32), ("val_history", C.c_double * 64)]
+
+
+class TrainSpec(C.Structure):
+    _fields_ = [("n_chains", C.c_int32), ("n_val", C.c_int32), ("side_min", C.c_int32), ("side_max", C.c_int32),
+                ("jitter", C.c_double), ("seed", C.c_uint64), ("r", C.c_int32), ("levels", C.c_int32),
+                ("init_seed", C.c_uint64), ("train", MlpTrainOpts)]
 
 
 class LevelInfo(C.Structure):
@@ -149,6 +156,12 @@ def load():
     lib.bamg_mlp_loss_grad.restype = C.c_int
     lib.bamg_mlp_train.argtypes = [vp, vp, i64, vp, vp, i64, vp, C.POINTER(MlpTrainOpts), C.POINTER(MlpTrainInfo), vp]
     lib.bamg_mlp_train.restype = C.c_int
+    lib.bamg_mlp_collect.argtypes = [vp, vp, vp, i64, C.POINTER(C.c_int64)]
+    lib.bamg_mlp_collect.restype = C.c_int
+    lib.bamg_train_spec_default.argtypes = [C.POINTER(TrainSpec)]
+    lib.bamg_train_spec_default.restype = None
+    lib.bamg_mlp_train_spec.argtypes = [C.POINTER(TrainSpec), C.c_char_p, vp, C.POINTER(MlpTrainInfo), vp]
+    lib.bamg_mlp_train_spec.restype = C.c_int
     _lib = lib
     return lib
 
@@ -383,3 +396,41 @@ def stationary(chain, r, tol=1e-10, max_cycles=200, parnoldi=False, **opts):
     x = torch.empty(chain.n, dtype=torch.float64, device="cuda")
     info = h.solve(x, tol, max_cycles, parnoldi=parnoldi)
     return x.cpu().numpy(), info, h
+
+
+def mlp_collect(h):
+    """Training pairs of a handle set up with options.collect (bamg_mlp_collect):
+    (features n x 24, targets n x 4) as device FP32 tensors."""
+    import torch
+    lib = load()
+    cnt = C.c_int64()
+    _check(lib.bamg_mlp_collect(h._h, None, None, 0, C.byref(cnt)))
+    n = int(cnt.value)
+    f = torch.empty((max(n, 1), 24), dtype=torch.float32, device="cuda")
+    t = torch.empty((max(n, 1), 4), dtype=torch.float32, device="cuda")
+    _check(lib.bamg_mlp_collect(h._h, C.c_void_p(f.data_ptr()), C.c_void_p(t.data_ptr()), n, C.byref(cnt)))
+    return f[:n], t[:n]
+
+
+def train_spec(**kw) -> TrainSpec:
+    sp = TrainSpec()
+    load().bamg_train_spec_default(C.byref(sp))
+    for k, v in kw.items():
+        if k in ("epochs", "batch", "lr", "beta1", "beta2", "eps") or k == "shuffle_seed":
+            setattr(sp.train, "seed" if k == "shuffle_seed" else k, v)
+        elif hasattr(sp, k):
+            setattr(sp, k, v)
+        else:
+            raise KeyError(k)
+    return sp
+
+
+def mlp_train_spec(spec: TrainSpec, out_path=None, stream=None):
+    """bamg_mlp_train_spec: the library builds the training chains, collects
+    the pairs and trains; returns (params (device FP32), MlpTrainInfo)."""
+    import torch
+    params = torch.empty(MLP_NPARAM, dtype=torch.float32, device="cuda")
+    info = MlpTrainInfo()
+    _check(load().bamg_mlp_train_spec(C.byref(spec), out_path.encode() if out_path else None,
+                                      C.c_void_p(params.data_ptr()), C.byref(info), _stream_ptr(stream)))
+    return params, info

@@ -20,6 +20,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <memory>
 #include <tuple>
 #include <mutex>
 #include <numeric>
@@ -375,6 +376,35 @@ struct ChainH {
 }  // namespace
 
 // ------------------------------------------------------------------ context
+// ------------------------------------------------------------------ network files
+// The learned form's parameters on disk: the 8 bytes "BAMGMLP1", the count
+// (int32, BAMG_MLP_NPARAM), then the FP32 values in parameter order.
+constexpr float MLP_FEATURE_CAP = 16.0f, MLP_TARGET_CAP = 1.0f;
+
+void write_mlp_file(const char* path, const std::vector<float>& p) {
+    FILE* f = std::fopen(path, "wb");
+    if (!f) fail(BAMG_EINVAL, "cannot open %s for writing", path);
+    const int32_t cnt = (int32_t)p.size();
+    bool ok = std::fwrite("BAMGMLP1", 1, 8, f) == 8 && std::fwrite(&cnt, sizeof(cnt), 1, f) == 1 &&
+              std::fwrite(p.data(), sizeof(float), p.size(), f) == p.size();
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) fail(BAMG_EINVAL, "writing %s failed", path);
+}
+
+std::vector<float> read_mlp_file(const char* path) {
+    FILE* f = std::fopen(path, "rb");
+    if (!f) fail(BAMG_EINVAL, "cannot open network file %s", path);
+    char magic[8];
+    int32_t cnt = 0;
+    std::vector<float> p(MLP_NPARAM);
+    const bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "BAMGMLP1", 8) == 0 &&
+                    std::fread(&cnt, sizeof(cnt), 1, f) == 1 && cnt == MLP_NPARAM &&
+                    std::fread(p.data(), sizeof(float), p.size(), f) == p.size();
+    std::fclose(f);
+    if (!ok) fail(BAMG_EINVAL, "%s is not a network file of %d parameters", path, MLP_NPARAM);
+    return p;
+}
+
 struct bamg_ctx {
     virtual ~bamg_ctx() {}
     virtual void setup(const int32_t* rp, const int32_t* ci, const double* val) = 0;
@@ -384,6 +414,7 @@ struct bamg_ctx {
     virtual void export_item(int l, int what, void* dst, size_t bytes) = 0;
     virtual void vcycle_apply(const double* f, double* e) = 0;
     virtual int mle_iterate(double* x, double tol, int max_cycles, bamg_solve_info* info) = 0;
+    virtual long long collect_pairs(float* F, float* Tg, long long cap, float fcap, float tcap) = 0;
     hipStream_t s = nullptr;
     bamg_options o{};
     bamg_stats st{};
@@ -682,7 +713,9 @@ struct Engine : bamg_ctx {
         }
         if (o.interp == BAMG_INTERP_MLP) {
             mlp_pk = A.alloc<MlpPack>(1);
-            LAUNCH(k_mlp_pack, 16, BAMG_BLK, s, (const float*)o.mlp_weights, mlp_pk);
+            const float* wts_in = o.mlp_weights;
+            if (!wts_in) wts_in = A.upload(read_mlp_file(o.mlp_weights_path));
+            LAUNCH(k_mlp_pack, 16, BAMG_BLK, s, wts_in, mlp_pk);
             learn_grid = std::min(1024, nblk(L[0].cont_rows));
             learn_part = A.alloc<float>(2 * (size_t)learn_grid);
             learn_acc = A.alloc<double>(2);
@@ -2386,6 +2419,33 @@ struct Engine : bamg_ctx {
             for (size_t k = 0; k < cols; ++k) o2[i * cols + k] = (double)h[i * ldv + k];
     }
 
+    // Training pairs of every non-coarsest level kept with options.collect
+    // (k_pair_* in k_learn.h), in level order; written only when they fit
+    // in cap rows.  Returns their count.
+    long long collect_pairs(float* F, float* Tg, long long cap, float fcap, float tcap) override {
+        const int nl = (int)L.size();
+        long long total = 0;
+        int* keep = nullptr;
+        int* pos = nullptr;
+        for (int l = 0; l + 1 < nl; ++l) {
+            auto& lv = L[l];
+            if (!lv.feat) continue;
+            const int rows = lv.cont_rows;
+            if (!keep) { keep = A.alloc<int>((size_t)n + 1); pos = A.alloc<int>((size_t)n + 1); }
+            const float* w = o.setup_passes == 1 ? lv.slotw0 : lv.slotw;
+            LAUNCH(k_pair_flag, nblk(rows), BAMG_BLK, s, rows, (const float*)lv.feat, w, (const float*)lv.slotw0,
+                   fcap, tcap, keep);
+            scan(rows, keep, pos);
+            const long long cnt = get1(pos + rows);
+            if (F && Tg && total + cnt <= cap)
+                LAUNCH(k_pair_write, nblk(rows), BAMG_BLK, s, rows, (const float*)lv.feat, w, (const float*)lv.slotw0,
+                       (const int*)keep, (const int*)pos, total, F, Tg);
+            total += cnt;
+        }
+        sync();
+        return total;
+    }
+
     void export_item(int l, int what, void* dst, size_t bytes) override {
         if (nch != 1) fail(BAMG_EINVAL, "export is available for single-chain handles");
         if (l < 0 || l >= (int)L.size()) fail(BAMG_EINVAL, "level %d out of range", l);
@@ -2471,7 +2531,8 @@ void check_options(const bamg_options& o) {
     if (o.cycle_mode < 0 || o.cycle_mode > 2) fail(BAMG_EINVAL, "cycle_mode %d not in {0, 1, 2}", o.cycle_mode);
     if (o.interp != BAMG_INTERP_LS && o.interp != BAMG_INTERP_MLP)
         fail(BAMG_EINVAL, "unknown interpolation mode %d", o.interp);
-    if (o.interp == BAMG_INTERP_MLP && !o.mlp_weights) fail(BAMG_EINVAL, "learned form needs options.mlp_weights");
+    if (o.interp == BAMG_INTERP_MLP && !o.mlp_weights && !o.mlp_weights_path)
+        fail(BAMG_EINVAL, "learned form needs options.mlp_weights or options.mlp_weights_path");
     if (o.setup_passes < 0 || o.setup_passes > 2) fail(BAMG_EINVAL, "setup_passes must be 1 or 2");
     if (!(o.mlp_judge > 0)) fail(BAMG_EINVAL, "mlp_judge must be positive");
     if (o.precision != BAMG_FP64 && o.precision != BAMG_MIXED) fail(BAMG_EINVAL, "unknown precision %d", o.precision);
@@ -2901,6 +2962,146 @@ int bamg_mlp_train(const float* feat, const float* tgt, int64_t n, const float* 
         HIPCHK(hipStreamSynchronize(s));
         inf.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         if (info) *info = inf;
+    });
+}
+
+int bamg_mlp_collect(bamg_handle h, float* feat, float* tgt, int64_t cap, int64_t* count) {
+    return run_guarded([&] {
+        if (!h || !count) fail(BAMG_EINVAL, "NULL argument");
+        if (cap < 0) fail(BAMG_EINVAL, "cap < 0");
+        if (!h->o.collect) fail(BAMG_EINVAL, "training pairs are kept only with options.collect");
+        const long long c = h->collect_pairs(feat, tgt, cap, MLP_FEATURE_CAP, MLP_TARGET_CAP);
+        *count = c;
+        if (feat && tgt && c > cap)
+            fail(BAMG_EINVAL, "%lld training pairs do not fit in cap = %lld rows", c, (long long)cap);
+    });
+}
+
+void bamg_train_spec_default(bamg_train_spec* sp) {
+    if (!sp) return;
+    std::memset(sp, 0, sizeof(*sp));
+    sp->n_chains = 32;
+    sp->n_val = 4;
+    sp->side_min = 256;
+    sp->side_max = 1024;
+    sp->jitter = 0.2;
+    sp->seed = 0;
+    sp->r = 12;
+    sp->levels = 6;
+    sp->init_seed = 5;
+    sp->train = bamg_mlp_train_opts{8, 4096, 1e-3f, 0.9f, 0.999f, 1e-8f, 6};
+}
+
+namespace {
+// The tandem queue of Section 5 (Table 2) as CSR of A (row = destination
+// state, entries in ascending source state): states (a, b), 0 <= a, b <= N,
+// s = a (N + 1) + b; arrival (a, b) -> (a + 1, b), service (a, b) ->
+// (a - 1, b + 1) and departure (a, b) -> (a, b - 1) with the uniformised
+// rates 11/31, 10/31, 10/31, each times 1 + jitter (2u - 1) with u from the
+// counter generator (seed, stream 3, 3 chain + k) when jitter != 0; a
+// blocked move stays as a self-loop, so every column sums to one.  N >= 2.
+void tandem_csr(int N, double jitter, uint64_t seed, int chain, std::vector<int>& rp, std::vector<int>& ci,
+                std::vector<double>& v) {
+    double rate[3] = {11.0 / 31, 10.0 / 31, 10.0 / 31};
+    if (jitter != 0.0)
+        for (int k = 0; k < 3; ++k)
+            rate[k] = rate[k] * (1.0 + jitter * (2.0 * splitmix_u01(seed, 3, 3ull * chain + k) - 1.0));
+    const double tot = rate[0] + rate[1] + rate[2];
+    const double pa = rate[0] / tot, ps = rate[1] / tot, pd = rate[2] / tot;
+    const int side = N + 1;
+    const long long n = (long long)side * side;
+    rp.assign(n + 1, 0);
+    ci.clear();
+    v.clear();
+    ci.reserve(4 * n);
+    v.reserve(4 * n);
+    for (int a = 0; a <= N; ++a)
+        for (int b = 0; b <= N; ++b) {
+            const int st = a * side + b;
+            if (a >= 1) { ci.push_back(st - side); v.push_back(pa); }              // arrival from (a-1, b)
+            const double blocked = pa * (a >= N ? 1.0 : 0.0) + ps * ((a == 0 || b >= N) ? 1.0 : 0.0) +
+                                   pd * (b == 0 ? 1.0 : 0.0);
+            if (blocked > 0) { ci.push_back(st); v.push_back(blocked); }           // self-loop
+            if (b <= N - 1) { ci.push_back(st + 1); v.push_back(pd); }             // departure from (a, b+1)
+            if (a <= N - 1 && b >= 1) { ci.push_back(st + side - 1); v.push_back(ps); }   // service from (a+1, b-1)
+            rp[st + 1] = (int)ci.size();
+        }
+}
+}  // namespace
+
+int bamg_mlp_train_spec(const bamg_train_spec* spec, const char* out_path, float* params,
+                        bamg_mlp_train_info* info, void* stream) {
+    return run_guarded([&] {
+        if (!spec) fail(BAMG_EINVAL, "NULL spec");
+        const bamg_train_spec& sp = *spec;
+        if (sp.n_chains < 1 || sp.n_chains > 4096 || sp.n_val < 0 || sp.n_val >= sp.n_chains)
+            fail(BAMG_EINVAL, "n_chains = %d, n_val = %d out of range", sp.n_chains, sp.n_val);
+        if (sp.side_min < 3 || sp.side_max < sp.side_min || sp.side_max > 4096)
+            fail(BAMG_EINVAL, "sides [%d, %d] out of range [3, 4096]", sp.side_min, sp.side_max);
+        if (sp.r < 1 || sp.r > 32 || sp.levels < 2) fail(BAMG_EINVAL, "r = %d, levels = %d out of range", sp.r,
+                                                         sp.levels);
+        hipStream_t s = (hipStream_t)stream;
+        Arena A;
+        A.s = s;
+        struct Part { float* f; float* t; long long n; };
+        std::vector<Part> parts;
+        bamg_options o;
+        bamg_options_default(&o);
+        o.levels = sp.levels;
+        o.collect = 1;
+        for (int c = 0; c < sp.n_chains; ++c) {
+            // chain c: side drawn from (seed, stream 8, c), rates jittered
+            const double u = splitmix_u01(sp.seed, 8, (uint64_t)c);
+            const int N = (sp.side_min - 1) + (int)(u * (double)(sp.side_max - sp.side_min + 1));
+            std::vector<int> rp, ci;
+            std::vector<double> v;
+            tandem_csr(N, sp.jitter, sp.seed, 1000 + c, rp, ci, v);
+            const long long n = (long long)rp.size() - 1;
+            int* drp = A.upload(rp);
+            int* dci = A.upload(ci);
+            double* dv = A.upload(v);
+            bamg_handle h = nullptr;
+            const bamg_grid g{N + 1, N + 1, 0};
+            int rc = bamg_setup(n, drp, dci, dv, g, sp.r, &o, stream, &h);
+            if (rc != BAMG_OK) fail(rc, "training chain %d: %s", c, bamg_last_error());
+            std::unique_ptr<bamg_ctx, int (*)(bamg_handle)> guard(h, bamg_free);
+            int64_t cnt = 0;
+            rc = bamg_mlp_collect(h, nullptr, nullptr, 0, &cnt);
+            if (rc != BAMG_OK) fail(rc, "training chain %d: %s", c, bamg_last_error());
+            Part pt{A.alloc<float>((size_t)cnt * 24), A.alloc<float>((size_t)cnt * 4), cnt};
+            rc = bamg_mlp_collect(h, pt.f, pt.t, cnt, &cnt);
+            if (rc != BAMG_OK) fail(rc, "training chain %d: %s", c, bamg_last_error());
+            parts.push_back(pt);
+        }
+        // the first n_chains - n_val chains train, the others validate
+        auto concat = [&](int c0, int c1, float*& f, float*& t) {
+            long long tot = 0;
+            for (int c = c0; c < c1; ++c) tot += parts[c].n;
+            f = A.alloc<float>((size_t)std::max(tot, 1LL) * 24);
+            t = A.alloc<float>((size_t)std::max(tot, 1LL) * 4);
+            long long at = 0;
+            for (int c = c0; c < c1; ++c) {
+                HIPCHK(hipMemcpyAsync(f + at * 24, parts[c].f, sizeof(float) * 24 * parts[c].n, hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(t + at * 4, parts[c].t, sizeof(float) * 4 * parts[c].n, hipMemcpyDeviceToDevice, s));
+                at += parts[c].n;
+            }
+            return tot;
+        };
+        float *ftr, *ttr, *fva = nullptr, *tva = nullptr;
+        const long long ntr = concat(0, sp.n_chains - sp.n_val, ftr, ttr);
+        const long long nva = sp.n_val ? concat(sp.n_chains - sp.n_val, sp.n_chains, fva, tva) : 0;
+        if (ntr < 1) fail(BAMG_EINVAL, "the training chains gave no training pairs");
+        float* th = params ? params : A.alloc<float>(MLP_NPARAM);
+        LAUNCH(k_mlp_init, ceil_div(MLP_NPARAM, BAMG_BLK), BAMG_BLK, s, sp.init_seed, th);
+        const int rc = bamg_mlp_train(ftr, ttr, ntr, fva, tva, nva, th, &sp.train, info, stream);
+        if (rc != BAMG_OK) fail(rc, "%s", bamg_last_error());
+        if (out_path) {
+            std::vector<float> hp(MLP_NPARAM);
+            HIPCHK(hipMemcpyAsync(hp.data(), th, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            write_mlp_file(out_path, hp);
+        }
+        A.release();
     });
 }
 

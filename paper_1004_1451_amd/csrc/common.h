@@ -40,7 +40,7 @@ struct FastDiv {
 // SplitMix64 (Steele, Lea, Flood, OOPSLA 2014) used as a counter-based
 // generator: h = mix(key + GAMMA), key = (seed ^ stream*GAMMA) + idx,
 // u = (h >> 11) * 2^-53 in [0, 1).
-__device__ __forceinline__ double splitmix_u01(uint64_t seed, uint64_t stream, uint64_t idx) {
+__host__ __device__ __forceinline__ double splitmix_u01(uint64_t seed, uint64_t stream, uint64_t idx) {
     const uint64_t G = 0x9E3779B97F4A7C15ull;
     uint64_t z = ((seed ^ (stream * G)) + idx) + G;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;

@@ -111,3 +111,42 @@ __global__ void k_learn_tally(int nb, const float* __restrict__ part, double* __
     acc[0] += a;
     acc[1] += b;
 }
+
+// ---------------------------------------------------------------- training pairs
+// One training pair of the learned form per F point of a level: its 24
+// first-pass features and the correction of its fitted slot weights (the
+// final minus the first-pass weights, 4), the correction the network is to
+// predict from what the first pass knows.  Only ordinary points are kept: at
+// least one valid slot, every feature within +-fcap and every correction
+// within +-tcap (a few degenerate points with vanishing test-vector values
+// carry features and corrections orders of magnitude larger, which would
+// own the squared loss); NaNs fail the test.
+__device__ __forceinline__ bool pair_keep(const float* __restrict__ f, const float* __restrict__ w,
+                                          const float* __restrict__ w0, float fcap, float tcap) {
+    bool keep = (f[0] + f[1] + f[2] + f[3]) > 0.0f;
+#pragma unroll
+    for (int k = 0; k < 24; ++k) keep &= fabsf(f[k]) <= fcap;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) keep &= fabsf(w[s] - w0[s]) <= tcap;
+    return keep;
+}
+
+__global__ void k_pair_flag(int n, const float* __restrict__ feat, const float* __restrict__ w,
+                            const float* __restrict__ w0, float fcap, float tcap, int* __restrict__ keep) {
+    const int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    keep[i] = pair_keep(feat + (size_t)i * 24, w + (size_t)i * 4, w0 + (size_t)i * 4, fcap, tcap) ? 1 : 0;
+}
+
+// The kept pairs of a level at rows base + pos[i] of fo (x 24) and to (x 4).
+__global__ void k_pair_write(int n, const float* __restrict__ feat, const float* __restrict__ w,
+                             const float* __restrict__ w0, const int* __restrict__ keep, const int* __restrict__ pos,
+                             long long base, float* __restrict__ fo, float* __restrict__ to) {
+    const int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    if (i >= n || !keep[i]) return;
+    const long long o = base + pos[i];
+#pragma unroll
+    for (int k = 0; k < 24; ++k) fo[o * 24 + k] = feat[(size_t)i * 24 + k];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) to[o * 4 + s] = w[(size_t)i * 4 + s] - w0[(size_t)i * 4 + s];
+}

@@ -163,15 +163,61 @@ def test_bad_learned_options():
     assert e.value.code == B.EINVAL
 
 
+def test_collect_is_the_filtered_export():
+    # bamg_mlp_collect: the F points' features and final - first-pass slot
+    # weights, ordinary points only (features within +-16, corrections within
+    # +-1), in level order -- the same rows the exported arrays give
+    ch = C.tandem_queue(40)
+    h = B.Hierarchy.from_chain(ch, 8, B.default_options(levels=3, collect=1))
+    fs, ts = [], []
+    for l in range(2):
+        n = h.level_info(l).n
+        F = h.export(l, B.X_FEATURES).reshape(n, 24)
+        T = h.export(l, B.X_SLOTW).reshape(n, 4) - h.export(l, B.X_SLOTW0).reshape(n, 4)
+        keep = (F[:, :4].sum(1) > 0) & (np.abs(F).max(1) <= 16) & (np.abs(T).max(1) <= 1)
+        fs.append(F[keep]); ts.append(T[keep])
+    f, t = B.mlp_collect(h)
+    assert np.array_equal(f.cpu().numpy(), np.concatenate(fs))
+    assert np.array_equal(t.cpu().numpy(), np.concatenate(ts))
+    h.close()
+    h2 = B.Hierarchy.from_chain(ch, 8, B.default_options(levels=3))
+    with pytest.raises(B.BamgError) as e:
+        B.mlp_collect(h2)
+    assert e.value.code == B.EINVAL
+
+
+def test_spec_training_is_the_manual_pipeline(tmp_path):
+    # bamg_mlp_train_spec builds the chains itself (the jittered tandem
+    # queues of the training set), collects and trains: the same parameters,
+    # bit for bit, as collecting from the generator module's chains and
+    # training through bamg_mlp_train
+    from paper_1004_1451_amd import learned as LRN
+    kw = dict(n_chains=3, n_val=1, side_min=40, side_max=60, r=8, levels=3, epochs=2, batch=1024)
+    path = str(tmp_path / "net.bin")
+    params, info = LRN.train(out_path=path, **kw)
+    chains = C.training_chains(3, n_min=39, n_max=59)
+    parts = [LRN.collect(ch, r=8, levels=3) for ch in chains]
+    ftr = torch.cat([p[0] for p in parts[:2]]); ttr = torch.cat([p[1] for p in parts[:2]])
+    fva, tva = parts[2]
+    th = B.mlp_init(5)
+    info2 = B.mlp_train(ftr, ttr, th, fva, tva, epochs=2, batch=1024, seed=6)
+    assert torch.equal(params, th)
+    assert info.steps == info2.steps and info.val_loss_last == info2.val_loss_last
+    # the network file gives the same learned setup as the device parameters
+    ch = C.tandem_queue(40)
+    base = dict(levels=3, interp=B.INTERP_MLP, stop_after=1)
+    h1 = B.Hierarchy.from_chain(ch, 8, B.default_options(**base, mlp_weights=params.data_ptr()))
+    h2 = B.Hierarchy.from_chain(ch, 8, B.default_options(**base, mlp_weights_path=path.encode()))
+    assert np.array_equal(h1.export(0, B.X_P_VAL), h2.export(0, B.X_P_VAL))
+
+
 def test_trained_network_gain_is_measured(record_property):
     # small version of the learned workload: train on jittered tandems, then
     # measure what the network changes on a held-out chain (reported, whatever
     # its sign): the distance of the level-0 weights to the final fit, and the
     # cycles and fallback share of the one-pass learned setup
     from paper_1004_1451_amd import learned as LRN
-    chains = C.training_chains(6, n_min=63, n_max=127)
-    params, info, sizes = LRN.train(chains, r=8, levels=4, n_val=2, epochs=4, batch=1024)
-    assert sizes[0] > 10000 and sizes[1] > 1000
+    params, info = LRN.train(n_chains=6, n_val=2, side_min=64, side_max=128, r=8, levels=4, epochs=4, batch=1024)
     assert info.val_loss_last < info.val_loss_first
     ev = C.tandem_queue(95, jitter=0.2, seed=7, chain_id=5)
     hf = B.Hierarchy.from_chain(ev, 8, B.default_options(levels=4, collect=1))
@@ -192,4 +238,8 @@ def test_trained_network_gain_is_measured(record_property):
     record_property("level0_weight_rms_to_final_fit", {"first_pass_fit": err_fit, "network": err_net})
     record_property("cycles_and_fallback", res)
     print("gain: weight rms to final fit %.5f (fit) -> %.5f (network); %s" % (err_fit, err_net, res))
-    assert err_net <= 1.5 * err_fit          # the correction never wrecks the fit
+    # what the learned form gains here is cycles of the one-pass setup (15 ->
+    # 10 on this held-out chain), not distance to the final weights: the
+    # network's rows are no closer to the recompute pass's fit than the first
+    # fit's are (0.0237 -> 0.0278 rms); both facts are recorded above
+    assert res["learned_1pass"][0] <= res["ls_1pass"][0]
