@@ -1372,7 +1372,10 @@ struct Engine : bamg_ctx {
             }
         }
         LAUNCH(k_cz_hess, nch, BAMG_WAVE, s, (const CoarseDesc*)cd, want, (const double*)Hh, HS, nsel, NS, sel_lam,
-               LSS, sel_s, SS);
+               LSS);
+        hipLaunchKernelGGL(k_cz_hess_vec, dim3(HSEL_THETA / 2, nch), dim3(BAMG_WAVE), 0, s, (const CoarseDesc*)cd,
+                           (const double*)Hh, HS, (const int*)nsel, NS, (const double*)sel_lam, LSS, sel_s, SS);
+        HIPCHK(hipGetLastError());
         std::vector<int> hs = getn(nsel, (size_t)nch * NS);
         int emax = 0;
         for (int c = 0; c < nch; ++c) {

@@ -1679,13 +1679,24 @@ k_hess_near0(int k, const int* __restrict__ act, const double* __restrict__ Hall
 // Chains without eigenpairs report no selection.
 __global__ void __launch_bounds__(BAMG_WAVE)
 k_cz_hess(const CoarseDesc* __restrict__ cd, int want, const double* __restrict__ Hh, int HS,
-          int* __restrict__ nsel, int NS, double* __restrict__ sel_lam, int LS, double* __restrict__ sel_s, int SS) {
+          int* __restrict__ nsel, int NS, double* __restrict__ sel_lam, int LS) {
     const int c = blockIdx.x;
     const CoarseDesc d = cd[c];
     if (d.am < 1 || want < 1) {
         if (threadIdx.x == 0) { nsel[(size_t)c * NS] = 0; nsel[(size_t)c * NS + 1] = 0; nsel[(size_t)c * NS + 2] = 0; }
         return;
     }
-    hessenberg_eig_body(d.am, want, Hh + (size_t)c * HS, nsel + (size_t)c * NS, sel_lam + (size_t)c * LS,
-                        sel_s + (size_t)c * SS);
+    hessenberg_select_body(d.am, want, Hh + (size_t)c * HS, nsel + (size_t)c * NS, sel_lam + (size_t)c * LS);
+}
+
+// The eigenvectors of the selected eigenvalues, one wavefront per entry e
+// (blockIdx.x) and chain (blockIdx.y), all at once.
+__global__ void __launch_bounds__(BAMG_WAVE)
+k_cz_hess_vec(const CoarseDesc* __restrict__ cd, const double* __restrict__ Hh, int HS, const int* __restrict__ nsel,
+              int NS, const double* __restrict__ sel_lam, int LS, double* __restrict__ sel_s, int SS) {
+    const int c = blockIdx.y, e = blockIdx.x;
+    const CoarseDesc d = cd[c];
+    if (d.am < 1 || e >= nsel[(size_t)c * NS] || nsel[(size_t)c * NS + 2]) return;
+    const double* th = sel_lam + (size_t)c * LS + HSEL_THETA + 2 * e;
+    hessenberg_vec_body(d.am, Hh + (size_t)c * HS, th[0], th[1], sel_s + (size_t)c * SS + (size_t)e * 2 * d.am);
 }

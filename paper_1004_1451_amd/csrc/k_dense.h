@@ -718,41 +718,32 @@ __device__ void hess_shift_apply_wave(int m, const double* U, const double* fm, 
 }
 
 // One wavefront: eigenvalues theta of H_m (Hessenberg, column-major (m+1) x m
-// in Hh), selection of the `want` nonzero lam = 1/theta of smallest |lam|
-// (largest |theta|; a conjugate pair counts as two and is never split, so one
-// more at a split; among equal moduli the member with Im(lam) > 0 first),
-// eigenvectors of H for the selected ones.  Outputs:
+// in Hh) and the selection of the `want` nonzero lam = 1/theta of smallest
+// |lam| (largest |theta|; a conjugate pair counts as two and is never split,
+// so one more at a split; among equal moduli the member with Im(lam) > 0
+// first).  Outputs:
 //   nsel_out[0] = selected entries, [1] = real columns they need, [2] = fail;
-//   sel_lam[2e..2e+1] = lam of entry e (Im >= 0 member of a pair);
-//   sel_s[e*2m + 2j..] = (re, im) of the eigenvector of H for entry e.
-// A row-major copy of H_m stays in LDS for the inverse iterations, whose
-// elimination reads one row per step.
-__device__ void hessenberg_eig_body(int m, int want, const double* __restrict__ Hh, int* __restrict__ nsel_out,
-                                    double* __restrict__ sel_lam, double* __restrict__ sel_s) {
+//   sel_lam[2e..2e+1] = lam of entry e (Im >= 0 member of a pair), and
+//   sel_lam[HSEL_THETA + 2e..] = its theta (the member with Im <= 0), from
+//   which hessenberg_vec_body finds the eigenvector.
+#define HSEL_THETA 16
+__device__ void hessenberg_select_body(int m, int want, const double* __restrict__ Hh, int* __restrict__ nsel_out,
+                                       double* __restrict__ sel_lam) {
     __shared__ double A[HQR_MAXM * HQR_LD];
-    __shared__ double Hs[HQR_MAXM * HQR_MAXM];
-    __shared__ double wr[HQR_MAXM], wi[HQR_MAXM], zr[HQR_MAXM], zi[HQR_MAXM], fm[2 * HQR_MAXM];
-    __shared__ int used[HQR_MAXM], swp[HQR_MAXM];
+    __shared__ double wr[HQR_MAXM], wi[HQR_MAXM];
+    __shared__ int used[HQR_MAXM];
     __shared__ int fail;
     const int lane = threadIdx.x;
     if (lane == 0) fail = 0;
-    double hn = 0;
-    for (int i = 0; i < m; ++i) {
-        double v = 0;
-        if (lane < m) v = (i <= lane + 1) ? Hh[(size_t)lane * (m + 1) + i] : 0.0;
-        if (lane < m) { A[i * HQR_LD + lane] = v; Hs[i * m + lane] = v; }
-        hn = fmax(hn, fabs(v));
-    }
-    // max over lanes
-#pragma unroll
-    for (int off = BAMG_WAVE / 2; off > 0; off >>= 1) hn = fmax(hn, __shfl_xor(hn, off, BAMG_WAVE));
+    for (int i = 0; i < m; ++i)
+        if (lane < m) A[i * HQR_LD + lane] = (i <= lane + 1) ? Hh[(size_t)lane * (m + 1) + i] : 0.0;
     if (lane < HQR_MAXM) used[lane] = 0;
     __threadfence_block();
     lds_sync();
     francis_eigvals_wave(m, A, wr, wi, &fail);
     lds_sync();
     int taken = 0, ne = 0, ncols = 0;
-    while (taken < want && !fail) {
+    while (taken < want && !fail && ne < HSEL_THETA / 2) {
         int best = -1;
         double bm = -1;
         for (int i = 0; i < m; ++i) {
@@ -774,27 +765,12 @@ __device__ void hessenberg_eig_body(int m, int want, const double* __restrict__ 
         }
         lds_sync();
         if (lane == 0) { used[best] = 1; if (pj >= 0) used[pj] = 1; }
-        if (lane < m) { zr[lane] = 1.0; zi[lane] = 0.0; }
-        lds_sync();
-        hess_shift_factor_wave(m, Hs, thr, thi, A, fm, swp, hn);
-        for (int itn = 0; itn < 3; ++itn) {
-            hess_shift_apply_wave(m, A, fm, swp, zr, zi);
-            double s = lane < m ? zr[lane] * zr[lane] + zi[lane] * zi[lane] : 0.0;
-            s = wave_sum(s);
-            s = __shfl(s, 0, BAMG_WAVE);
-            double nr = sqrt(s);
-            lds_sync();
-            if (lane < m) { zr[lane] /= nr; zi[lane] /= nr; }
-            lds_sync();
-        }
-        double den = thr * thr + thi * thi;
+        const double den = thr * thr + thi * thi;
         if (lane == 0) {
             sel_lam[2 * ne] = thr / den;
             sel_lam[2 * ne + 1] = pair ? -thi / den : 0.0;
-        }
-        if (lane < m) {
-            sel_s[(size_t)ne * m * 2 + 2 * lane] = zr[lane];
-            sel_s[(size_t)ne * m * 2 + 2 * lane + 1] = pair ? zi[lane] : 0.0;
+            sel_lam[HSEL_THETA + 2 * ne] = thr;
+            sel_lam[HSEL_THETA + 2 * ne + 1] = thi;
         }
         ++ne;
         ncols += pair ? 2 : 1;
@@ -802,6 +778,48 @@ __device__ void hessenberg_eig_body(int m, int want, const double* __restrict__ 
         lds_sync();
     }
     if (lane == 0) { nsel_out[0] = ne; nsel_out[1] = ncols; nsel_out[2] = fail; }
+}
+
+// One wavefront: the eigenvector of H_m (column-major (m+1) x m in Hh) for
+// the eigenvalue theta = (thr, thi), by three steps of inverse iteration
+// with H - theta I from the start vector of ones, each normalised to
+// ||z||_2 = 1; (re, im) pairs into out[2j..2j+1] (im = 0 for a real theta).
+// A row-major copy of H_m stays in LDS for the elimination, which reads one
+// row per step.
+__device__ void hessenberg_vec_body(int m, const double* __restrict__ Hh, double thr, double thi,
+                                    double* __restrict__ out) {
+    __shared__ double U[HQR_MAXM * HQR_LD];
+    __shared__ double Hs[HQR_MAXM * HQR_MAXM];
+    __shared__ double zr[HQR_MAXM], zi[HQR_MAXM], fm[2 * HQR_MAXM];
+    __shared__ int swp[HQR_MAXM];
+    const int lane = threadIdx.x;
+    double hn = 0;
+    for (int i = 0; i < m; ++i) {
+        double v = 0;
+        if (lane < m) v = (i <= lane + 1) ? Hh[(size_t)lane * (m + 1) + i] : 0.0;
+        if (lane < m) Hs[i * m + lane] = v;
+        hn = fmax(hn, fabs(v));
+    }
+#pragma unroll
+    for (int off = BAMG_WAVE / 2; off > 0; off >>= 1) hn = fmax(hn, __shfl_xor(hn, off, BAMG_WAVE));
+    if (lane < m) { zr[lane] = 1.0; zi[lane] = 0.0; }
+    __threadfence_block();
+    lds_sync();
+    hess_shift_factor_wave(m, Hs, thr, thi, U, fm, swp, hn);
+    for (int itn = 0; itn < 3; ++itn) {
+        hess_shift_apply_wave(m, U, fm, swp, zr, zi);
+        double s = lane < m ? zr[lane] * zr[lane] + zi[lane] * zi[lane] : 0.0;
+        s = wave_sum(s);
+        s = __shfl(s, 0, BAMG_WAVE);
+        const double nr = sqrt(s);
+        lds_sync();
+        if (lane < m) { zr[lane] /= nr; zi[lane] /= nr; }
+        lds_sync();
+    }
+    if (lane < m) {
+        out[2 * lane] = zr[lane];
+        out[2 * lane + 1] = thi != 0.0 ? zi[lane] : 0.0;
+    }
 }
 
 // One wavefront: the eigenvalue of the leading k x k block of a Hessenberg
