@@ -462,6 +462,7 @@ struct Engine : bamg_ctx {
     double *Wp = nullptr, *Fp = nullptr, *ypool = nullptr, *cpool = nullptr, *bcolp = nullptr, *t1 = nullptr,
            *t2 = nullptr, *rre = nullptr, *rim = nullptr, *gtpart = nullptr;
     float* Wfp = nullptr;
+    double *dcP = nullptr, *dcR = nullptr, *dcmp = nullptr;
     double *scale = nullptr, *minpiv = nullptr, *cy = nullptr, *csc = nullptr, *dots = nullptr, *vyb = nullptr,
            *npart = nullptr;
     double *Vb = nullptr, *Hh = nullptr, *sel_lam = nullptr, *sel_s = nullptr;
@@ -834,7 +835,11 @@ struct Engine : bamg_ctx {
         for (double** p : {&ypool, &cpool, &bcolp, &t1, &t2, &rre, &rim}) *p = A.alloc<double>(NVt);
         gtpart = A.alloc<double>((size_t)ceil_div(maxnL, GT_RCH) * NVt);
         scale = A.alloc<double>(nch);
-        minpiv = A.alloc<double>(3 * (size_t)nch);   // per chain, then two half-factorisation partials
+        minpiv = A.alloc<double>(nch);
+        // divide and conquer: left and right panels, pivot partials
+        dcP = A.alloc<double>((size_t)NVt * 2 * GJ_NB);
+        dcR = A.alloc<double>((size_t)NVt * GJ_NB);
+        dcmp = A.alloc<double>((size_t)nch * DC_MP);
         cy = A.alloc<double>(nch);
         csc = A.alloc<double>((size_t)nch * SCS);
         const int am = std::max(1, AMmax);
@@ -1221,13 +1226,23 @@ struct Engine : bamg_ctx {
                 if (d.n < 2) continue;
                 if (d.periodic && d.nx >= 3) arrow = true; else plain = true;
             }
-            // chains without the arrow: the twisted factorisation, top and
-            // bottom halves at once, then the middle block row
+            // chains without the arrow: divide and conquer over the block
+            // rows, the diagonal blocks' inverses joined level by level
             if (plain) {
-                hipLaunchKernelGGL(k_cz_lu_half, dim3(2, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cds, Fp,
-                                   (const double*)scale, minpiv + nch);
-                hipLaunchKernelGGL(k_cz_lu_mid, dim3(nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cds, Fp,
-                                   (const double*)scale, (const double*)(minpiv + nch), minpiv);
+                hipLaunchKernelGGL(k_dc_leaf, dim3(nxmax, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cds, Fp, Wp,
+                                   (const double*)scale, dcmp);
+                for (int t = 0; (1 << t) < nxmax; ++t) {
+                    const int joins = ceil_div(nxmax - (1 << t), 2 << t), side = std::min(2 << t, nxmax);
+                    hipLaunchKernelGGL(k_dc_core, dim3(joins, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cds, t, Fp,
+                                       (const double*)Wp, dcmp);
+                    hipLaunchKernelGGL(k_dc_panels, dim3(nxmax, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cds, t,
+                                       Fp, (const double*)Wp, dcP, dcR, NVt);
+                    hipLaunchKernelGGL(k_dc_tiles, dim3(joins * side * side, nch), dim3(BAMG_BLK), 0, s,
+                                       (const CoarseDesc*)cds, t, (const double*)dcP, (const double*)dcR, NVt, Wp);
+                    HIPCHK(hipGetLastError());
+                }
+                hipLaunchKernelGGL(k_dc_minpiv, dim3(nch), dim3(BAMG_WAVE), 0, s, (const CoarseDesc*)cds,
+                                   (const double*)dcmp, minpiv);
             }
             if (arrow) {
                 const dim3 gl(4, nch);
@@ -1244,9 +1259,6 @@ struct Engine : bamg_ctx {
             HIPCHK(hipGetLastError());
             if (arrow)
                 hipLaunchKernelGGL(k_cz_subst, dim3(ceil_div(maxnL, CZ_SUB_TC), nch), dim3(BAMG_BLK), 0, s,
-                                   (const CoarseDesc*)cds, Wp, (const double*)Fp);
-            if (plain)
-                hipLaunchKernelGGL(k_cz_subst_tw, dim3(ceil_div(maxnL, CZ_SUB_TC), 2, nch), dim3(BAMG_BLK), 0, s,
                                    (const CoarseDesc*)cds, Wp, (const double*)Fp);
             HIPCHK(hipGetLastError());
             if (bordered) bordered_inverse();

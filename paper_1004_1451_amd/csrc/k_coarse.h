@@ -4,9 +4,10 @@
 // dense / vector storage inside the pools.
 //
 // Per chain (n = n_L, Section 4.2 and Algorithm 3 with l = L):
-//   W  = B_L^+ (n x n, row-major)         formed from the block LU of the
+//   W  = B_L^+ (n x n, row-major)         formed from the inverse of the
 //        padded operator [[B_11, 0], [0, 1]] (block tridiagonal in grid rows,
-//        blocks of b = ny <= 64, plus the corner blocks when periodic), then
+//        blocks of b = ny <= 64, plus the corner blocks when periodic: block
+//        LU and substitution with those, divide and conquer without), then
 //        W = Pi_y [[B_11^-1, 0], [0, 0]] Pi_1;
 //   y  spans null(B_L); c = T_L^T 1; cy = c^T y;
 //   Arnoldi on v -> u - y (c^T u)/cy, u = W T_L v, for the coarsest
@@ -354,7 +355,7 @@ k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, 
     const int K = d.nx - 1, q = blockIdx.x;
     const int kk = k < 0 ? K : k;
     if (d.n < 2 || (k >= 0 && k >= K)) return;
-    if (!(d.periodic && d.nx >= 3)) return;  // factored by k_cz_lu_half and k_cz_lu_mid
+    if (!(d.periodic && d.nx >= 3)) return;  // inverted by divide and conquer (k_dc_*)
     if (q > 0) {
         if (kk >= 1)
             cz_elim_part(d, kk - 1, 1, q, Fp, (double(*)[GJ_NB + 2])lds, (double(*)[GJ_NB + 2])(lds + GJ_NB * (GJ_NB + 2)));
@@ -409,170 +410,8 @@ k_cz_lu_step(const CoarseDesc* __restrict__ cd, int k, double* __restrict__ Fp, 
     if (tid == 0) minpiv[blockIdx.y] = fmin(minpiv[blockIdx.y], mp);
 }
 
-// Twisted block factorisation of a chain without the arrow, two workgroups
-// per chain (grid (2, chains)) that run at the same time: with m = (K+1)/2,
-// workgroup 0 eliminates block rows 0 .. m-1 from the top,
-//   S_0 = D_0,  S_k = D_k - M_k U_{k-1},  M_{k+1} = L_{k+1} S_k^-1,
-// and workgroup 1 rows K .. m+1 from the bottom,
-//   R_K = D_K,  R_k = D_k - N_k L_{k+1},  N_{k-1} = U_{k-1} R_k^-1,
-// so the dependent chain of block inversions is half as long.  S_k^-1 and
-// R_k^-1 replace D_k; M_k (k = 1 .. m) replaces L_k, N_k (k = m .. K-1)
-// replaces U_k; the U_k above row m and the L_k below it stay as they are.
-// Products with the banded U and L take their 3 band terms in ascending
-// order; the multiplier being formed is kept in LDS for the next row, and the
-// next diagonal block is loaded before the current Gauss-Jordan.  Each
-// workgroup leaves its smallest pivot in mpart[2 c + half]; k_cz_lu_mid
-// inverts the middle block row.  Chains with the arrow return at once.
-__global__ void __launch_bounds__(BAMG_BLK)
-k_cz_lu_half(const CoarseDesc* __restrict__ cd, double* __restrict__ Fp, const double* __restrict__ scale,
-             double* __restrict__ mpart) {
-    __shared__ double Ms[GJ_NB][GJ_NB + 1];
-    __shared__ double Bs[GJ_NB][GJ_NB + 2];
-    __shared__ __align__(16) double prow[2][2][GJ_NB];
-    __shared__ double lob[GJ_NB][3];
-    const int ch = blockIdx.y, half = blockIdx.x;
-    const CoarseDesc d = cd[ch];
-    double mp = 1e300;
-    if (d.n < 2 || (d.periodic && d.nx >= 3)) {
-        if (threadIdx.x == 0) mpart[2 * ch + half] = mp;
-        return;
-    }
-    const int K = d.nx - 1, m = (K + 1) / 2, b = d.ny, tid = threadIdx.x;
-    const int c = tid % BAMG_WAVE, w = tid / BAMG_WAVE;
-    const int first = half == 0 ? 0 : K, cnt = half == 0 ? m : K - m, step = half == 0 ? 1 : -1;
-    // the coupling to the previous row of the sequence (top: U_{k-1}; bottom:
-    // L_{k+1}) and the banded block the next multiplier comes from (top:
-    // L_{k+1} -> M_{k+1}; bottom: U_{k-1} -> N_{k-1})
-    const int pslot = half == 0 ? 1 : 2, nslot = half == 0 ? 2 : 1;
-    const double sc = scale[ch];
-    double Dn[CZ_GJ_ROWS];
-    if (cnt > 0) {
-        const double* D0 = cz_blk(Fp, d, 0, first);
-#pragma unroll
-        for (int i = 0; i < CZ_GJ_ROWS; ++i) {
-            const int r = CZ_GJ_ROWS * w + i;
-            Dn[i] = (r < b && c < b) ? D0[r * b + c] : 0.0;
-        }
-    }
-    int tc[3];
-    cz_band(c, b, d.periodic, tc);
-    for (int it = 0; it < cnt; ++it) {
-        const int kk = first + step * it;
-        double* D = cz_blk(Fp, d, 0, kk);
-        double* Nx = cz_blk(Fp, d, nslot, kk + step);
-        if (tid < 3 * GJ_NB) {
-            const int r = tid / 3, sl = tid % 3;
-            int t[3];
-            cz_band(r, b, d.periodic, t);
-            lob[r][sl] = (r < b && t[sl] >= 0) ? Nx[r * b + t[sl]] : 0.0;
-        }
-        double u[3] = {0.0, 0.0, 0.0};
-        if (it >= 1) {
-            const double* Pv = cz_blk(Fp, d, pslot, kk - step);
-#pragma unroll
-            for (int sl = 0; sl < 3; ++sl) u[sl] = (c < b && tc[sl] >= 0) ? Pv[tc[sl] * b + c] : 0.0;
-        }
-        double S[CZ_GJ_ROWS];
-#pragma unroll
-        for (int i = 0; i < CZ_GJ_ROWS; ++i) {
-            const int r = CZ_GJ_ROWS * w + i;
-            double acc = 0.0;
-            if (it >= 1) {
-#pragma unroll
-                for (int sl = 0; sl < 3; ++sl)
-                    if (r < b && c < b && tc[sl] >= 0) acc = fma(Ms[r][tc[sl]], u[sl], acc);
-            }
-            S[i] = (r < b && c < b) ? Dn[i] - acc : (r == c ? 1.0 : 0.0);
-        }
-        // the next diagonal block, while this one is inverted
-        if (it + 1 < cnt) {
-            const double* D1 = cz_blk(Fp, d, 0, kk + step);
-#pragma unroll
-            for (int i = 0; i < CZ_GJ_ROWS; ++i) {
-                const int r = CZ_GJ_ROWS * w + i;
-                Dn[i] = (r < b && c < b) ? D1[r * b + c] : 0.0;
-            }
-        }
-        cz_gj(S, w, c, b, sc, mp, prow);
-#pragma unroll
-        for (int i = 0; i < CZ_GJ_ROWS; ++i) {
-            const int r = CZ_GJ_ROWS * w + i;
-            if (r < b && c < b) D[r * b + c] = S[i];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < CZ_GJ_ROWS; ++i) Bs[CZ_GJ_ROWS * w + i][c] = S[i];
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < CZ_GJ_ROWS; ++i) {
-            const int r = CZ_GJ_ROWS * w + i;
-            if (!(r < b && c < b)) continue;
-            int t[3];
-            cz_band(r, b, d.periodic, t);
-            double acc = 0.0;
-#pragma unroll
-            for (int sl = 0; sl < 3; ++sl)
-                if (t[sl] >= 0) acc = fma(lob[r][sl], Bs[t[sl]][c], acc);
-            Nx[r * b + c] = acc;
-            Ms[r][c] = acc;
-        }
-        __syncthreads();
-    }
-    if (tid == 0) mpart[2 * ch + half] = mp;
-}
-
-// The middle block row of the twisted factorisation (one workgroup per
-// chain, after k_cz_lu_half):  Z = D_m - M_m U_{m-1} - N_m L_{m+1} (each
-// term present when its side has rows), Z^-1 replaces D_m; minpiv[c] takes
-// the smallest pivot of the three parts.
-__global__ void __launch_bounds__(BAMG_BLK)
-k_cz_lu_mid(const CoarseDesc* __restrict__ cd, double* __restrict__ Fp, const double* __restrict__ scale,
-            const double* __restrict__ mpart, double* __restrict__ minpiv) {
-    __shared__ __align__(16) double prow[2][2][GJ_NB];
-    const int ch = blockIdx.x;
-    const CoarseDesc d = cd[ch];
-    if (d.n < 2 || (d.periodic && d.nx >= 3)) return;
-    const int K = d.nx - 1, m = (K + 1) / 2, b = d.ny, tid = threadIdx.x;
-    const int c = tid % BAMG_WAVE, w = tid / BAMG_WAVE;
-    int tc[3];
-    cz_band(c, b, d.periodic, tc);
-    double* D = cz_blk(Fp, d, 0, m);
-    double S[CZ_GJ_ROWS];
-#pragma unroll
-    for (int i = 0; i < CZ_GJ_ROWS; ++i) {
-        const int r = CZ_GJ_ROWS * w + i;
-        S[i] = (r < b && c < b) ? D[r * b + c] : (r == c ? 1.0 : 0.0);
-    }
-    for (int side = 0; side < 2; ++side) {
-        if (side == 0 ? m < 1 : m >= K) continue;
-        const double* Mm = cz_blk(Fp, d, side == 0 ? 2 : 1, m);           // M_m or N_m (dense)
-        const double* Pv = cz_blk(Fp, d, side == 0 ? 1 : 2, side == 0 ? m - 1 : m + 1);   // U_{m-1} or L_{m+1}
-        double u[3];
-#pragma unroll
-        for (int sl = 0; sl < 3; ++sl) u[sl] = (c < b && tc[sl] >= 0) ? Pv[tc[sl] * b + c] : 0.0;
-#pragma unroll
-        for (int i = 0; i < CZ_GJ_ROWS; ++i) {
-            const int r = CZ_GJ_ROWS * w + i;
-            if (!(r < b && c < b)) continue;
-            double acc = 0.0;
-#pragma unroll
-            for (int sl = 0; sl < 3; ++sl)
-                if (tc[sl] >= 0) acc = fma(Mm[r * b + tc[sl]], u[sl], acc);
-            S[i] -= acc;
-        }
-    }
-    double mp = 1e300;
-    cz_gj(S, w, c, b, scale[ch], mp, prow);
-#pragma unroll
-    for (int i = 0; i < CZ_GJ_ROWS; ++i) {
-        const int r = CZ_GJ_ROWS * w + i;
-        if (r < b && c < b) D[r * b + c] = S[i];
-    }
-    if (tid == 0) minpiv[ch] = fmin(minpiv[ch], fmin(mp, fmin(mpart[2 * ch], mpart[2 * ch + 1])));
-}
-
 // All substitution steps of W = (L U)^-1 for a chain with the arrow (the
-// others take k_cz_subst_tw), for one tile of CZ_SUB_TC columns
+// others take the divide and conquer below), for one tile of CZ_SUB_TC columns
 // of one chain per workgroup (grid (ceil(n / CZ_SUB_TC), nch)): the columns of
 // W are independent right-hand sides (the identity), so a workgroup walks
 // every block row on its own, with the previous block row of the solution
@@ -642,7 +481,7 @@ k_cz_subst(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const dou
     const int c0 = blockIdx.x * CZ_SUB_TC;
     if (n < 2 || c0 >= n) return;
     const bool arrow = d.periodic && d.nx >= 3;
-    if (!arrow) return;                              // k_cz_subst_tw takes those chains
+    if (!arrow) return;                              // k_dc_* invert those chains
     const double* F = Fp + d.boff;
     double* W = Wp + d.woff;
     const int w = min(CZ_SUB_TC, n - c0);
@@ -752,229 +591,398 @@ k_cz_subst(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const dou
     }
 }
 
-// The substitution for chains without the arrow, on the twisted factors of
-// k_cz_lu_half / k_cz_lu_mid (m = (K+1)/2), for one tile of CZ_SUB_TC
-// columns of W per pair of workgroups (grid (tiles, 2, chains)):
-//   Y_s = I_s - M_s Y_{s-1}  (s = s0 .. m-1, Y = 0 above the tile's first
-//         identity block s0),
-//   V_s = I_s - N_s V_{s+1}  (s = s1 .. m+1, V = 0 below its last one s1),
-//   X_m = Z^-1 (I_m - M_m Y_{m-1} - N_m V_{m+1}),
-//   X_k = S_k^-1 (Y_k - U_k X_{k+1})  (k = m-1 .. 0; workgroup side 0),
-//   X_k = R_k^-1 (V_k - L_k X_{k-1})  (k = m+1 .. K; side 1).
-// Both workgroups of a tile form the forward parts and X_m; each stores and
-// finishes its own half of the block rows (side 0 also row m), so the chain
-// of dependent block products is about half that of one sweep over all rows.
-// The banded U_k and L_k take their 3 band terms per row in ascending column
-// order, read from memory one step ahead; the dense 64 x 64 by 64 x 16
-// products run on the FP64 matrix cores (cz_mac_mfma), whose operands come
-// from LDS two values per lane per block product.
-__device__ int cz_subst_tw_sequence(int K, int m, int s0, int s1, int side, int* seq) {
-    const bool top = s0 <= m - 1, bot = s1 >= m + 1;
-    int q = 0;
-    if (top)
-        for (int s = s0 + 1; s <= m - 1; ++s) seq[q++] = 2 * (K + 1) + s;       // M_s
-    if (bot)
-        for (int s = s1 - 1; s >= m + 1; --s) seq[q++] = (K + 1) + s;           // N_s
-    if (top) seq[q++] = 2 * (K + 1) + m;                                          // M_m
-    if (bot) seq[q++] = (K + 1) + m;                                              // N_m
-    seq[q++] = m;                                                                 // Z^-1
-    if (side == 0)
-        for (int k = m - 1; k >= 0; --k) seq[q++] = k;                            // S_k^-1
-    else
-        for (int k = m + 1; k <= K; ++k) seq[q++] = k;                            // R_k^-1
-    return q;
+// ---------------------------------------------------------------- divide and conquer
+// Inverse of the block tridiagonal operator of a chain without the arrow by
+// divide and conquer over its block rows.  The leaves are the diagonal
+// blocks, W[k, k] = D_k^-1.  Level t joins the segment X = [a, m), m = a +
+// 2^t (a a multiple of 2^(t+1)), with Y = [m, e), e = min(a + 2^(t+1), nx),
+// whose inverses Xi and Yi are in place in W.  X and Y are coupled only by
+// E = U_{m-1} (block (m-1, m)) and F = L_m (block (m, m-1)), so the Schur
+// complement Y - F Xi E differs from Y in its first block alone:
+//   C = L_m Xi[m-1, m-1] U_{m-1},  G = Yi[m, m],  K = (I - C G)^-1 C
+// (the Woodbury formula: its inverse is Yi + Yi[:, m] K Yi[m, :]).  With the
+// block column P1 = Xi[:, m-1] U_{m-1}, the block row R1 = L_m Xi[m-1, :],
+// P2 = Yi[:, m] and R2 = Yi[m, :], the inverse of the joined segment is
+//   [[Xi + P1 (G + G K G) R1,  -P1 (I + G K) R2],
+//    [-P2 (I + K G) R1,         Yi + P2 K R2    ]].
+// The chain of dependent inversions is 1 + ceil(log2 nx) long (a leaf, then
+// one I - C G per level) instead of the nx block rows of an elimination.
+// Three launches per level: k_dc_core (C, G, K per join, one workgroup),
+// k_dc_panels (per block row: the left panels P1 (G + G K G), -P1 (I + G K),
+// -P2 (I + K G), P2 K and the right panels R1, R2) and k_dc_tiles (each b x b
+// tile of a joined segment: W = (W or 0) + left panel rows x right panel
+// columns).  Dense 64 x 64 products run on the FP64 matrix cores; the
+// banded U and L take their band terms in ascending order.  Smallest pivots:
+// the leaves' relative to max |B_L| and the joins' I - C G (dimensionless)
+// into dmp[chain DC_MP + k] and [chain DC_MP + nx + m].
+#define DC_MP (2 * CZ_MAX_NX)
+
+__device__ __forceinline__ bool dc_plain(const CoarseDesc& d) { return d.n >= 2 && !(d.periodic && d.nx >= 3); }
+
+// The join q of level t: X = [a, m), Y = [m, e); false when Y is empty.
+struct DcJoin { int a, m, e; };
+__device__ __forceinline__ bool dc_join(int nx, int t, int q, DcJoin& g) {
+    g.a = q << (t + 1);
+    g.m = g.a + (1 << t);
+    g.e = min(g.a + (2 << t), nx);
+    return g.m < nx;
 }
 
-// Row set of a thread in k_cz_subst_tw: wave wv, lane l keeps rows
-// 16 wv + l / 16 + 4 a (a = 0..3) of column l % 16 of the tile, the layout
-// in which v_mfma_f64_16x16x4f64 returns a wave's 16 x 16 product (lane l,
-// register a: row l / 16 + 4 a, column l % 16; its operands: lane l holds
-// A[l % 16][l / 16] and B[l / 16][l % 16] of the 16 x 4 and 4 x 16 blocks).
-typedef double cz_d4 __attribute__((ext_vector_type(4)));
-
-// acc (+)= sign Ms[rows of this wave, 0:64] * Xs[0:64, column]: 16 products
-// of 16 x 4 by 4 x 16 blocks in ascending k (the zero padding beyond b
-// adds nothing).
-__device__ __forceinline__ void cz_mac_mfma(const double (*Ms)[GJ_NB + 1], const double (*Xs)[CZ_SUB_TC + 1], int wv,
-                                            int lane, double acc[4], double sign) {
-    cz_d4 c = {acc[0], acc[1], acc[2], acc[3]};
+// acc[cb] (+)= A[16 wv + rows, 0:64] B[0:64, 16 cb + columns], cb = 0..3, by
+// v_mfma_f64_16x16x4f64 in ascending k: lane l, register q of acc[cb] holds
+// row 16 wv + l / 16 + 4 q, column 16 cb + l % 16 (the layout the
+// instruction returns; its operands: lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16] of the 16 x 4 and 4 x 16 blocks).
+typedef double dc_d4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void dc_mfma(const double (*A)[GJ_NB + 1], const double (*B)[GJ_NB + 1], int wv, int lane,
+                                        dc_d4 (&acc)[4]) {
     const int ar = 16 * wv + lane % 16, kq = lane / 16, bc = lane % 16;
 #pragma unroll
     for (int kk = 0; kk < GJ_NB / 4; ++kk) {
-        const double av = Ms[ar][4 * kk + kq];
-        const double bv = sign * Xs[4 * kk + kq][bc];
-        c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
+        const double av = A[ar][4 * kk + kq];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+            acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, B[4 * kk + kq][16 * cb + bc], acc[cb], 0, 0, 0);
+    }
+}
+__device__ __forceinline__ void dc_zero(dc_d4 (&acc)[4]) {
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = dc_d4{0.0, 0.0, 0.0, 0.0};
+}
+__device__ __forceinline__ int dc_row(int wv, int lane, int q) { return 16 * wv + lane / 16 + 4 * q; }
+__device__ __forceinline__ int dc_col(int lane, int cb) { return 16 * cb + lane % 16; }
+
+// Stage two 64 x 64 matrices into LDS, entry (r, c) from f1(r, c) and
+// f2(r, c): every load of a thread is issued before its LDS stores.
+template <typename F1, typename F2>
+__device__ __forceinline__ void dc_stage2(double (*D1)[GJ_NB + 1], F1 f1, double (*D2)[GJ_NB + 1], F2 f2) {
+    constexpr int Q = GJ_NB * GJ_NB / BAMG_BLK;
+    double v1[Q], v2[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int e = threadIdx.x + q * BAMG_BLK;
+        v1[q] = f1(e / GJ_NB, e % GJ_NB);
+        v2[q] = f2(e / GJ_NB, e % GJ_NB);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = c[q];
+    for (int q = 0; q < Q; ++q) {
+        const int e = threadIdx.x + q * BAMG_BLK;
+        D1[e / GJ_NB][e % GJ_NB] = v1[q];
+        D2[e / GJ_NB][e % GJ_NB] = v2[q];
+    }
 }
 
+// Leaves: W[k, k] = D_k^-1 (grid (block rows, chains)).
 __global__ void __launch_bounds__(BAMG_BLK)
-k_cz_subst_tw(const CoarseDesc* __restrict__ cd, double* __restrict__ Wp, const double* __restrict__ Fp) {
-    static_assert(BAMG_BLK == 256 && CZ_SUB_TC == 16 && GJ_NB == 64, "four waves of 16 x 16 on a 64 x 16 tile");
-    __shared__ double Ms[GJ_NB][GJ_NB + 1];
-    __shared__ double Xs[GJ_NB][CZ_SUB_TC + 1];
-    __shared__ double Ks[GJ_NB][CZ_SUB_TC + 1];
-    __shared__ int seq[2 * CZ_MAX_NX + 8];
-    __shared__ int nseq;
-    const CoarseDesc d = cd[blockIdx.z];
-    const int side = blockIdx.y;
-    const int K = d.nx - 1, b = d.ny, n = d.n, m = (K + 1) / 2;
-    const int c0 = blockIdx.x * CZ_SUB_TC;
-    if (n < 2 || c0 >= n || (d.periodic && d.nx >= 3)) return;
-    const double* F = Fp + d.boff;
+k_dc_leaf(const CoarseDesc* __restrict__ cd, double* __restrict__ Fp, double* __restrict__ Wp,
+          const double* __restrict__ scale, double* __restrict__ dmp) {
+    static_assert(CZ_GJ_THREADS == BAMG_BLK, "one Gauss-Jordan block per workgroup");
+    __shared__ __align__(16) double prow[2][2][GJ_NB];
+    const int ch = blockIdx.y, k = blockIdx.x;
+    const CoarseDesc d = cd[ch];
+    if (!dc_plain(d) || k >= d.nx) return;
+    const int b = d.ny, n = d.n, c = threadIdx.x % BAMG_WAVE, w = threadIdx.x / BAMG_WAVE;
+    const double* D = cz_blk(Fp, d, 0, k);
+    double S[CZ_GJ_ROWS];
+#pragma unroll
+    for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+        const int r = CZ_GJ_ROWS * w + i;
+        S[i] = (r < b && c < b) ? D[r * b + c] : (r == c ? 1.0 : 0.0);
+    }
+    double mp = 1e300;
+    cz_gj(S, w, c, b, scale[ch], mp, prow);
     double* W = Wp + d.woff;
-    const int w = min(CZ_SUB_TC, n - c0);
-    const int s0 = c0 / b, s1 = (c0 + w - 1) / b;
-    const bool top = s0 <= m - 1, bot = s1 >= m + 1;
-    const int tid = threadIdx.x, wv = tid / BAMG_WAVE, lane = tid % BAMG_WAVE, tc = lane % 16;
-    int rows[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) rows[q] = 16 * wv + lane / 16 + 4 * q;
-    const long long bb = (long long)b * b;
-    if (tid == 0) nseq = cz_subst_tw_sequence(K, m, s0, s1, side, seq);
+    for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+        const int r = CZ_GJ_ROWS * w + i;
+        if (r < b && c < b) W[(size_t)(k * b + r) * n + k * b + c] = S[i];
+    }
+    if (threadIdx.x == 0) dmp[(size_t)ch * DC_MP + k] = mp;
+}
+
+// One join of level t per workgroup (grid (joins, chains)): C, G and
+// K = (I - C G)^-1 C into block slots 3 and 4 of the join's index (free on
+// chains without the arrow).
+__global__ void __launch_bounds__(BAMG_BLK)
+k_dc_core(const CoarseDesc* __restrict__ cd, int t, double* __restrict__ Fp, const double* __restrict__ Wp,
+          double* __restrict__ dmp) {
+    __shared__ double Xs[GJ_NB][GJ_NB + 1];     // Xi[m-1, m-1], then X U, then I - C G, then its inverse
+    __shared__ double Gs[GJ_NB][GJ_NB + 1];
+    __shared__ double Cs[GJ_NB][GJ_NB + 1];
+    __shared__ __align__(16) double prow[2][2][GJ_NB];
+    const int ch = blockIdx.y;
+    const CoarseDesc d = cd[ch];
+    DcJoin g;
+    if (!dc_plain(d) || !dc_join(d.nx, t, blockIdx.x, g)) return;
+    const int b = d.ny, n = d.n, tid = threadIdx.x, c = tid % BAMG_WAVE, w = tid / BAMG_WAVE;
+    const double* W = Wp + d.woff;
+    const int x0 = (g.m - 1) * b, y0 = g.m * b;
+    const double* U = cz_blk(Fp, d, 1, g.m - 1);
+    const double* L = cz_blk(Fp, d, 2, g.m);
+    int tc[3];
+    cz_band(c, b, d.periodic, tc);
+    double uc[3];
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) uc[sl] = (c < b && tc[sl] >= 0) ? U[tc[sl] * b + c] : 0.0;
+    dc_stage2(
+        Xs, [&](int r, int cc) { return (r < b && cc < b) ? W[(size_t)(x0 + r) * n + x0 + cc] : 0.0; },
+        Gs, [&](int r, int cc) { return (r < b && cc < b) ? W[(size_t)(y0 + r) * n + y0 + cc] : 0.0; });
     __syncthreads();
-    double pre[GJ_NB * GJ_NB / BAMG_BLK];
-    int sidx = 0;
-    auto fetch = [&](int i) {
-        const double* M = F + (long long)seq[i] * bb;
+    // X U: column c of U holds its band rows tc
+    double T[CZ_GJ_ROWS];
 #pragma unroll
-        for (int q = 0; q < GJ_NB * GJ_NB / BAMG_BLK; ++q) {
-            const int e = tid + q * BAMG_BLK, r = e / GJ_NB, c = e % GJ_NB;
-            pre[q] = (r < b && c < b) ? M[r * b + c] : 0.0;
-        }
-    };
-    auto next_block = [&]() {
+    for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+        const int r = CZ_GJ_ROWS * w + i;
+        double acc = 0.0;
 #pragma unroll
-        for (int q = 0; q < GJ_NB * GJ_NB / BAMG_BLK; ++q) {
-            const int e = tid + q * BAMG_BLK;
-            Ms[e / GJ_NB][e % GJ_NB] = pre[q];
-        }
-        if (++sidx < nseq) fetch(sidx);
-    };
-    fetch(0);
-    auto ident = [&](int blk, double X[4]) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) X[q] = (rows[q] < b && tc < w && blk * b + rows[q] == c0 + tc) ? 1.0 : 0.0;
-    };
-    auto put = [&](const double X[4], double (*Ys)[CZ_SUB_TC + 1]) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Ys[rows[q]][tc] = X[q];
-    };
-    auto store = [&](int blk, const double X[4]) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (rows[q] < b && tc < w) W[(size_t)(blk * b + rows[q]) * n + c0 + tc] = X[q];
-    };
-    double T[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) T[q] = 0.0;
-    // rows of this side's half whose forward part is zero
-    if (side == 0)
-        for (int s = 0; s < min(s0, m); ++s) store(s, T);
-    else
-        for (int s = max(s1 + 1, m + 1); s <= K; ++s) store(s, T);
-    // forward from the top: Y_{m-1} ends in Ks
-    if (top) {
-        for (int s = s0; s <= m - 1; ++s) {
-            ident(s, T);
-            if (s > s0) {                            // Xs holds Y_{s-1}
-                __syncthreads();
-                next_block();                        // M_s
-                __syncthreads();
-                cz_mac_mfma(Ms, Xs, wv, lane, T, -1.0);
-            }
-            __syncthreads();
-            put(T, Xs);
-            if (side == 0) store(s, T);
-        }
-        put(T, Ks);
-    }
-    // forward from the bottom: V_{m+1} ends in Xs
-    if (bot) {
-        for (int s = s1; s >= m + 1; --s) {
-            ident(s, T);
-            if (s < s1) {                            // Xs holds V_{s+1}
-                __syncthreads();
-                next_block();                        // N_s
-                __syncthreads();
-                cz_mac_mfma(Ms, Xs, wv, lane, T, -1.0);
-            }
-            __syncthreads();
-            put(T, Xs);
-            if (side == 1) store(s, T);
-        }
-    }
-    // middle block row
-    ident(m, T);
-    if (top) {
-        __syncthreads();
-        next_block();                                // M_m
-        __syncthreads();
-        cz_mac_mfma(Ms, Ks, wv, lane, T, -1.0);
-    }
-    if (bot) {
-        __syncthreads();
-        next_block();                                // N_m
-        __syncthreads();
-        cz_mac_mfma(Ms, Xs, wv, lane, T, -1.0);
+        for (int sl = 0; sl < 3; ++sl)
+            if (tc[sl] >= 0) acc = fma(Xs[r][tc[sl]], uc[sl], acc);
+        T[i] = acc;
     }
     __syncthreads();
-    next_block();                                    // Z^-1
-    put(T, Xs);
+#pragma unroll
+    for (int i = 0; i < CZ_GJ_ROWS; ++i) Xs[CZ_GJ_ROWS * w + i][c] = T[i];
     __syncthreads();
-    double X[4];
+    // C = L (X U): row r of L holds its band columns
 #pragma unroll
-    for (int q = 0; q < 4; ++q) X[q] = 0.0;
-    cz_mac_mfma(Ms, Xs, wv, lane, X, 1.0);
-    if (side == 0) store(m, X);
+    for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+        const int r = CZ_GJ_ROWS * w + i;
+        int tr[3];
+        cz_band(r, b, d.periodic, tr);
+        double acc = 0.0;
+        if (r < b) {
+#pragma unroll
+            for (int sl = 0; sl < 3; ++sl)
+                if (tr[sl] >= 0) acc = fma(L[r * b + tr[sl]], Xs[tr[sl]][c], acc);
+        }
+        Cs[r][c] = acc;
+    }
     __syncthreads();
-    put(X, Xs);                                      // X_m
-    // this side's half, outwards from row m; U_k (side 0) or L_k (side 1)
-    // banded, its 3 band terms per row read one step ahead
-    const int slot = side == 0 ? 1 : 2, dk = side == 0 ? -1 : 1;
-    const int kfirst = m + dk, cntk = side == 0 ? m : K - m;
-    double ub[4][3];
-    int tb[4][3];
+    // I - C G (the identity beyond b: C and G are zero there)
+    dc_d4 acc[4];
+    dc_zero(acc);
+    dc_mfma(Cs, Gs, w, c, acc);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) cz_band(rows[q], b, d.periodic, tb[q]);
-    auto load_band = [&](int k) {
-        const double* P = F + (long long)(slot * (K + 1) + k) * bb;
+    for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < 4; ++q) {
+            const int row = dc_row(w, c, q), col = dc_col(c, cb);
+            Xs[row][col] = (row == col ? 1.0 : 0.0) - acc[cb][q];
+        }
+    __syncthreads();
+    double S[CZ_GJ_ROWS];
+#pragma unroll
+    for (int i = 0; i < CZ_GJ_ROWS; ++i) S[i] = Xs[CZ_GJ_ROWS * w + i][c];
+    double mp = 1e300;
+    cz_gj(S, w, c, b, 1.0, mp, prow);
+#pragma unroll
+    for (int i = 0; i < CZ_GJ_ROWS; ++i) Xs[CZ_GJ_ROWS * w + i][c] = S[i];
+    __syncthreads();
+    dc_zero(acc);
+    dc_mfma(Xs, Cs, w, c, acc);                 // K = (I - C G)^-1 C
+    double* Ko = cz_blk(Fp, d, 3, blockIdx.x);
+    double* Go = cz_blk(Fp, d, 4, blockIdx.x);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = dc_row(w, c, q), col = dc_col(c, cb);
+            if (row < b && col < b) Ko[row * b + col] = acc[cb][q];
+        }
+    for (int e = tid; e < b * b; e += BAMG_BLK) Go[e] = Gs[e / b][e % b];
+    if (tid == 0) dmp[(size_t)ch * DC_MP + d.nx + g.m] = mp;
+}
+
+// The panels of level t for one block row k of a joined segment (grid
+// (block rows, chains)).  Left panels, row i of the chain at
+// Pp[(voff + i) 2 GJ_NB + side GJ_NB + s] for the X columns (side 0) and the
+// Y columns (side 1); right panels at Rp[s rld + voff + j] for column j.
+__global__ void __launch_bounds__(BAMG_BLK)
+k_dc_panels(const CoarseDesc* __restrict__ cd, int t, double* __restrict__ Fp, const double* __restrict__ Wp,
+            double* __restrict__ Pp, double* __restrict__ Rp, int rld) {
+    __shared__ double Gs[GJ_NB][GJ_NB + 1];
+    __shared__ double Ks[GJ_NB][GJ_NB + 1];
+    __shared__ double As[GJ_NB][GJ_NB + 1];     // P1 or P2 rows, then P1 G K
+    __shared__ double Qs[GJ_NB][GJ_NB + 1];     // P1 G or P2 K
+    const int ch = blockIdx.y, k = blockIdx.x;
+    const CoarseDesc d = cd[ch];
+    DcJoin g;
+    if (!dc_plain(d) || k >= d.nx || !dc_join(d.nx, t, k >> (t + 1), g)) return;
+    const bool xside = k < g.m;
+    const int b = d.ny, n = d.n, tid = threadIdx.x, c = tid % BAMG_WAVE, w = tid / BAMG_WAVE;
+    const double* W = Wp + d.woff;
+    const double* Kq = cz_blk(Fp, d, 3, k >> (t + 1));
+    const double* Gq = cz_blk(Fp, d, 4, k >> (t + 1));
+    dc_stage2(Gs, [&](int r, int cc) { return (r < b && cc < b) ? Gq[r * b + cc] : 0.0; },
+              Ks, [&](int r, int cc) { return (r < b && cc < b) ? Kq[r * b + cc] : 0.0; });
+    const int r0 = k * b;
+    if (xside) {
+        // P1 = Xi[rows, m-1] U_{m-1}; R1 = L_m Xi[m-1, columns]
+        const double* U = cz_blk(Fp, d, 1, g.m - 1);
+        const double* L = cz_blk(Fp, d, 2, g.m);
+        const int x0 = (g.m - 1) * b;
+        int tc[3];
+        cz_band(c, b, d.periodic, tc);
+        double uc[3];
+#pragma unroll
+        for (int sl = 0; sl < 3; ++sl) uc[sl] = (c < b && tc[sl] >= 0) ? U[tc[sl] * b + c] : 0.0;
+        // every load of the thread first, then the band sums
+        // (column r0 + c of Xi's block row m - 1 at the band rows of L's row r)
+        double wr[CZ_GJ_ROWS][3], lr[CZ_GJ_ROWS][3], wl[CZ_GJ_ROWS][3];
+        int ts[CZ_GJ_ROWS][3];
+#pragma unroll
+        for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+            const int r = CZ_GJ_ROWS * w + i;
+            cz_band(r, b, d.periodic, ts[i]);
 #pragma unroll
             for (int sl = 0; sl < 3; ++sl) {
-                const int t = tb[q][sl];
-                ub[q][sl] = (rows[q] < b && t >= 0) ? P[rows[q] * b + t] : 0.0;
+                const bool tin = r < b && c < b && tc[sl] >= 0, sin = r < b && c < b && ts[i][sl] >= 0;
+                wr[i][sl] = tin ? W[(size_t)(r0 + r) * n + x0 + tc[sl]] : 0.0;
+                lr[i][sl] = sin ? L[r * b + ts[i][sl]] : 0.0;
+                wl[i][sl] = sin ? W[(size_t)(x0 + ts[i][sl]) * n + r0 + c] : 0.0;
             }
-    };
-    if (cntk > 0) load_band(kfirst);
-    for (int it = 0; it < cntk; ++it) {
-        const int k = kfirst + dk * it;
-        double U[4];
+        }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            U[q] = (rows[q] < b && tc < w) ? W[(size_t)(k * b + rows[q]) * n + c0 + tc] : 0.0;
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+            const int r = CZ_GJ_ROWS * w + i;
+            double acc = 0.0, acr = 0.0;
 #pragma unroll
             for (int sl = 0; sl < 3; ++sl) {
-                const int t = tb[q][sl];
-                if (rows[q] < b && t >= 0) U[q] = fma(ub[q][sl], -1.0 * Xs[t][tc], U[q]);
+                if (tc[sl] >= 0) acc = fma(wr[i][sl], uc[sl], acc);
+                if (ts[i][sl] >= 0) acr = fma(lr[i][sl], wl[i][sl], acr);
             }
-        if (it + 1 < cntk) load_band(k + dk);
+            As[r][c] = acc;
+            if (c < b) Rp[(size_t)r * rld + d.voff + r0 + c] = acr;
+        }
+    } else {
+        // P2 = Yi[rows, m]; R2 = Yi[m, columns]
+        const int y0 = g.m * b;
+        double pr[CZ_GJ_ROWS], rr[CZ_GJ_ROWS];
+#pragma unroll
+        for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+            const int r = CZ_GJ_ROWS * w + i;
+            pr[i] = (r < b && c < b) ? W[(size_t)(r0 + r) * n + y0 + c] : 0.0;
+            rr[i] = (r < b && c < b) ? W[(size_t)(y0 + r) * n + r0 + c] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < CZ_GJ_ROWS; ++i) {
+            const int r = CZ_GJ_ROWS * w + i;
+            As[r][c] = pr[i];
+            if (c < b) Rp[(size_t)r * rld + d.voff + r0 + c] = rr[i];
+        }
+    }
+    __syncthreads();
+    double* P = Pp + (size_t)(d.voff + r0) * (2 * GJ_NB);
+    dc_d4 a1[4], a2[4];
+    dc_zero(a1);
+    dc_zero(a2);
+    if (xside) {
+        dc_mfma(As, Gs, w, c, a1);              // P1 G
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Qs[dc_row(w, c, q)][dc_col(c, cb)] = a1[cb][q];
         __syncthreads();
-        next_block();                                // S_k^-1 or R_k^-1
-        put(U, Xs);
+        dc_mfma(Qs, Ks, w, c, a2);              // P1 G K
+        // -P1 (I + G K) for the Y columns
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = dc_row(w, c, q), col = dc_col(c, cb);
+                if (row < b) P[(size_t)row * 2 * GJ_NB + GJ_NB + col] = -(As[row][col] + a2[cb][q]);
+            }
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 4; ++q) T[q] = 0.0;
-        cz_mac_mfma(Ms, Xs, wv, lane, T, 1.0);
-        store(k, T);
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) As[dc_row(w, c, q)][dc_col(c, cb)] = a2[cb][q];
         __syncthreads();
-        put(T, Xs);
+        dc_zero(a1);
+        dc_mfma(As, Gs, w, c, a1);              // P1 G K G
+        // P1 (G + G K G) for the X columns
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = dc_row(w, c, q), col = dc_col(c, cb);
+                if (row < b) P[(size_t)row * 2 * GJ_NB + col] = Qs[row][col] + a1[cb][q];
+            }
+    } else {
+        dc_mfma(As, Ks, w, c, a1);              // P2 K for the Y columns
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = dc_row(w, c, q), col = dc_col(c, cb);
+                Qs[row][col] = a1[cb][q];
+                if (row < b) P[(size_t)row * 2 * GJ_NB + GJ_NB + col] = a1[cb][q];
+            }
+        __syncthreads();
+        dc_mfma(Qs, Gs, w, c, a2);              // P2 K G
+        // -P2 (I + K G) for the X columns
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = dc_row(w, c, q), col = dc_col(c, cb);
+                if (row < b) P[(size_t)row * 2 * GJ_NB + col] = -(As[row][col] + a2[cb][q]);
+            }
     }
+}
+
+// The tiles of level t: grid (joins S^2, chains) with S = min(2^(t+1), nx);
+// tile (I, J) of join q: W[I, J] = (W[I, J] if I and J are on the same side,
+// else 0) + left panel rows of I for J's side times the right panel columns
+// of J.
+__global__ void __launch_bounds__(BAMG_BLK)
+k_dc_tiles(const CoarseDesc* __restrict__ cd, int t, const double* __restrict__ Pp, const double* __restrict__ Rp,
+           int rld, double* __restrict__ Wp) {
+    __shared__ double As[GJ_NB][GJ_NB + 1];
+    __shared__ double Bs[GJ_NB][GJ_NB + 1];
+    const CoarseDesc d = cd[blockIdx.y];
+    if (!dc_plain(d)) return;
+    const int S = min(2 << t, d.nx);
+    const int q = blockIdx.x / (S * S), loc = blockIdx.x % (S * S);
+    DcJoin g;
+    if (!dc_join(d.nx, t, q, g)) return;
+    const int I = g.a + loc / S, J = g.a + loc % S;
+    if (I >= g.e || J >= g.e) return;
+    const int side = J >= g.m ? 1 : 0;
+    const bool same = (I >= g.m ? 1 : 0) == side;
+    const int b = d.ny, n = d.n, tid = threadIdx.x, c = tid % BAMG_WAVE, w = tid / BAMG_WAVE;
+    const double* P = Pp + (size_t)(d.voff + I * b) * (2 * GJ_NB) + side * GJ_NB;
+    dc_stage2(As, [&](int r, int cc) { return r < b ? P[(size_t)r * 2 * GJ_NB + cc] : 0.0; },
+              Bs, [&](int r, int cc) { return (r < b && cc < b) ? Rp[(size_t)r * rld + d.voff + J * b + cc] : 0.0; });
+    __syncthreads();
+    dc_d4 acc[4];
+    dc_zero(acc);
+    dc_mfma(As, Bs, w, c, acc);
+    double* W = Wp + d.woff;
+#pragma unroll
+    for (int q2 = 0; q2 < 4; ++q2)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const int row = dc_row(w, c, q2), col = dc_col(c, cb);
+            if (row < b && col < b) {
+                const size_t o = (size_t)(I * b + row) * n + J * b + col;
+                W[o] = (same ? W[o] : 0.0) + acc[cb][q2];
+            }
+        }
+}
+
+// minpiv[chain] = min(minpiv, the leaves' and joins' smallest pivots); one
+// wavefront per chain.
+__global__ void k_dc_minpiv(const CoarseDesc* __restrict__ cd, const double* __restrict__ dmp,
+                            double* __restrict__ minpiv) {
+    const CoarseDesc d = cd[blockIdx.x];
+    if (!dc_plain(d)) return;
+    double v = 1e300;
+    for (int i = threadIdx.x; i < 2 * d.nx; i += BAMG_WAVE)
+        if (i != d.nx) v = fmin(v, dmp[(size_t)blockIdx.x * DC_MP + i]);
+#pragma unroll
+    for (int o = BAMG_WAVE / 2; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, BAMG_WAVE));
+    if (threadIdx.x == 0) minpiv[blockIdx.x] = fmin(minpiv[blockIdx.x], v);
 }
 
 // ---------------------------------------------------------------- bordered grids
