@@ -462,7 +462,7 @@ struct Engine : bamg_ctx {
     double *Wp = nullptr, *Fp = nullptr, *ypool = nullptr, *cpool = nullptr, *bcolp = nullptr, *t1 = nullptr,
            *t2 = nullptr, *rre = nullptr, *rim = nullptr, *gtpart = nullptr;
     float* Wfp = nullptr;
-    double *dcP = nullptr, *dcR = nullptr, *dcmp = nullptr;
+    double *dcP = nullptr, *dcR = nullptr, *dcmp = nullptr, *apart = nullptr, *arn_u = nullptr;
     double *scale = nullptr, *minpiv = nullptr, *cy = nullptr, *csc = nullptr, *dots = nullptr, *vyb = nullptr,
            *npart = nullptr;
     double *Vb = nullptr, *Hh = nullptr, *sel_lam = nullptr, *sel_s = nullptr;
@@ -854,6 +854,8 @@ struct Engine : bamg_ctx {
         dots = A.alloc<double>((size_t)nch * DS);
         vyb = A.alloc<double>((size_t)nch * DS);
         npart = A.alloc<double>((size_t)nch * nblk(std::max(1, maxnL)) * 2);
+        apart = A.alloc<double>((size_t)nch * DS * nblk(std::max(1, maxnL)));
+        arn_u = A.alloc<double>(std::max(1, NVt));
     }
 
     // The coarsest descriptors after the coarsest operators moved (a level
@@ -1341,25 +1343,49 @@ struct Engine : bamg_ctx {
         }
     }
 
-    // u (column j+1 of every chain's basis): u -= y (c^T u)/cy, two rounds
-    // of classical Gram-Schmidt against columns 0..j, normalise (H[j+1, j]).
-    void project_and_normalize(int j) {
+    // The start vector (basis column 0): u -= y (c^T u)/cy, normalised.
+    void arnoldi_start() {
         const dim3 gv(nblk(maxnL), nch);
-        // the projection against c with the first Gram-Schmidt pass, then the
-        // second pass, then the norm
+        hipLaunchKernelGGL(k_cz_arn_dots2, dim3(1, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, -1,
+                           (const double*)cpool, (const double*)Vb, dots, DS);
+        hipLaunchKernelGGL(k_cz_arn_update2, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, -1, (const double*)ypool,
+                           (const double*)cy, (const double*)dots, (const double*)vyb, DS, Vb, Hh, HS, npart);
+        hipLaunchKernelGGL(k_cz_arn_normalize, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, -1, Vb, Hh, HS, vyb, DS,
+                           (const double*)npart);
+        HIPCHK(hipGetLastError());
+    }
+
+    // Step j >= 0 after the product u = W T v_j in column j+1: the projection
+    // against c with the first Gram-Schmidt pass, the second pass, the norm;
+    // t1 = T v_{j+1} for the next step.  K = j + 1 rounded up to 8.
+    template <typename F>
+    static void arn_dispatch(int j, F&& f) {
+        switch ((j + 8) / 8) {
+            case 1: f(std::integral_constant<int, 8>{}); break;
+            case 2: f(std::integral_constant<int, 16>{}); break;
+            case 3: f(std::integral_constant<int, 24>{}); break;
+            case 4: f(std::integral_constant<int, 32>{}); break;
+            case 5: f(std::integral_constant<int, 40>{}); break;
+            case 6: f(std::integral_constant<int, 48>{}); break;
+            case 7: f(std::integral_constant<int, 56>{}); break;
+            default: f(std::integral_constant<int, 64>{}); break;
+        }
+    }
+    void arnoldi_orthogonalize(int j) {
+        static_assert(HQR_MAXM <= 64, "Arnoldi steps beyond the widest accumulator set");
+        const dim3 gv(nblk(maxnL), nch);
         hipLaunchKernelGGL(k_cz_arn_dots2, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j,
                            (const double*)cpool, (const double*)Vb, dots, DS);
-        hipLaunchKernelGGL(k_cz_arn_update2, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, (const double*)ypool,
-                           (const double*)cy, (const double*)dots, (const double*)vyb, DS, Vb, Hh, HS, npart);
-        if (j >= 0) {
-            hipLaunchKernelGGL(k_cz_arn_dots, dim3(j + 1, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j,
-                               (const double*)Vb, dots, DS);
-            hipLaunchKernelGGL(k_cz_arn_update, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, (const double*)ypool,
-                               (const double*)dots, DS, Vb, Hh, HS, npart);
-        }
-        HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_cz_arn_normalize, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, Vb, Hh, HS, vyb, DS,
-                           (const double*)npart);
+        arn_dispatch(j, [&](auto kc) {
+            constexpr int K = decltype(kc)::value;
+            hipLaunchKernelGGL(k_cz_arn_update2p<K>, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j,
+                               (const double*)ypool, (const double*)cy, (const double*)dots, (const double*)vyb, DS, Vb,
+                               Hh, HS, apart);
+            hipLaunchKernelGGL(k_cz_arn_updatep<K>, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j,
+                               (const double*)ypool, (const double*)apart, DS, (const double*)Vb, Hh, HS, arn_u, npart);
+        });
+        hipLaunchKernelGGL(k_cz_arn_normtv<T>, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, (const double*)arn_u,
+                           Vb, Hh, HS, vyb, DS, (const double*)npart, t1);
         HIPCHK(hipGetLastError());
     }
 
@@ -1372,15 +1398,14 @@ struct Engine : bamg_ctx {
             zero(Hh, sizeof(double) * nch * HS);
             hipLaunchKernelGGL(k_cz_arn_start, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, o.seed, Vb);
             HIPCHK(hipGetLastError());
-            // the start vector is basis column 0: project and normalise it as
-            // "column j + 1" with j = -1 (no H entry)
-            project_and_normalize(-1);
+            // the start vector is basis column 0 (no H entry), then t1 = T v_0
+            arnoldi_start();
+            hipLaunchKernelGGL(k_cz_tv<T>, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, 0, (const double*)Vb, t1);
             for (int j = 0; j < AMmax; ++j) {
-                hipLaunchKernelGGL(k_cz_tv<T>, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, (const double*)Vb, t1);
                 hipLaunchKernelGGL(k_cz_arn_gemv, gw, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, (const double*)Wp,
                                    (const double*)t1, Vb);
                 HIPCHK(hipGetLastError());
-                project_and_normalize(j);
+                arnoldi_orthogonalize(j);
             }
         }
         LAUNCH(k_cz_hess, nch, BAMG_WAVE, s, (const CoarseDesc*)cd, want, (const double*)Hh, HS, nsel, NS, sel_lam,

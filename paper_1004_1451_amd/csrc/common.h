@@ -84,6 +84,44 @@ __device__ __forceinline__ void wave_sum_many(double (&a)[K]) {
     wave_sum_halve<K, K / 2, BAMG_WAVE / 2>(a, threadIdx.x % BAMG_WAVE);
 }
 
+// Reduction scratch of the passes (per wave: the KR + 2 sums of a row block).
+template <int K>
+struct GsRed { static constexpr int KR = K <= 8 ? 8 : K <= 16 ? 16 : K <= 32 ? 32 : 64; };
+
+// Partial sums of a block for several dots at once: K accumulators per
+// thread (K <= 64) reduced per wavefront by butterfly exchanges on the next
+// power of two KR of K (so a dot's summation order depends only on KR), then
+// the four wave totals in order.  Writes nb + 2 values, d < nb: acc[d],
+// d = nb: ey, d = nb + 1: ex, to part[((blockIdx.y NDM) + d) gridDim.x +
+// blockIdx.x].  red: (BAMG_BLK / BAMG_WAVE) (KR + 2) doubles of LDS.
+template <int K>
+__device__ __forceinline__ void gs_store_partials(double (&acc_k)[K], double ey, double ex, int nb,
+                                                  double* __restrict__ part, int NDM, double* red) {
+    // the lane reduction runs on the next power of two (8 .. 64) of K, so a
+    // dot's summation order depends only on that power, not on K itself
+    constexpr int KR = K <= 8 ? 8 : K <= 16 ? 16 : K <= 32 ? 32 : 64;
+    constexpr int SH = KR >= 64 ? 0 : KR >= 32 ? 1 : KR >= 16 ? 2 : 3;
+    static_assert((BAMG_WAVE >> SH) == KR && K <= KR, "K must be at most 64");
+    double acc[KR];
+#pragma unroll
+    for (int b = 0; b < KR; ++b) acc[b] = b < K ? acc_k[b] : 0.0;
+    const int lane = threadIdx.x % BAMG_WAVE, wv = threadIdx.x / BAMG_WAVE;
+    wave_sum_many<KR>(acc);
+    ey = wave_sum(ey);
+    ex = wave_sum(ex);
+    if ((lane & ((1 << SH) - 1)) == 0) red[wv * (KR + 2) + (lane >> SH)] = acc[0];
+    if (lane == 0) { red[wv * (KR + 2) + KR] = ey; red[wv * (KR + 2) + KR + 1] = ex; }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < nb + 2) {
+        const int src = t < nb ? t : KR + (t - nb);
+        double v = 0;
+#pragma unroll
+        for (int q = 0; q < BAMG_BLK / BAMG_WAVE; ++q) v += red[q * (KR + 2) + src];
+        part[((size_t)blockIdx.y * NDM + t) * gridDim.x + blockIdx.x] = v;
+    }
+}
+
 // Sum over a block of BAMG_BLK threads in a fixed order (lane tree, then the
 // four wave totals in order).  Result valid in thread 0.
 template <typename T>

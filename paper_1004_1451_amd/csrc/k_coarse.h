@@ -952,22 +952,28 @@ k_dc_tiles(const CoarseDesc* __restrict__ cd, int t, const double* __restrict__ 
     const bool same = (I >= g.m ? 1 : 0) == side;
     const int b = d.ny, n = d.n, tid = threadIdx.x, c = tid % BAMG_WAVE, w = tid / BAMG_WAVE;
     const double* P = Pp + (size_t)(d.voff + I * b) * (2 * GJ_NB) + side * GJ_NB;
+    double* W = Wp + d.woff + (size_t)(I * b) * n + J * b;
+    // the tile's current entries first (same side), in flight with the panels
+    double old[4][4];
+#pragma unroll
+    for (int q2 = 0; q2 < 4; ++q2)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const int row = dc_row(w, c, q2), col = dc_col(c, cb);
+            old[q2][cb] = (same && row < b && col < b) ? W[(size_t)row * n + col] : 0.0;
+        }
     dc_stage2(As, [&](int r, int cc) { return r < b ? P[(size_t)r * 2 * GJ_NB + cc] : 0.0; },
               Bs, [&](int r, int cc) { return (r < b && cc < b) ? Rp[(size_t)r * rld + d.voff + J * b + cc] : 0.0; });
     __syncthreads();
     dc_d4 acc[4];
     dc_zero(acc);
     dc_mfma(As, Bs, w, c, acc);
-    double* W = Wp + d.woff;
 #pragma unroll
     for (int q2 = 0; q2 < 4; ++q2)
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
             const int row = dc_row(w, c, q2), col = dc_col(c, cb);
-            if (row < b && col < b) {
-                const size_t o = (size_t)(I * b + row) * n + J * b + col;
-                W[o] = (same ? W[o] : 0.0) + acc[cb][q2];
-            }
+            if (row < b && col < b) W[(size_t)row * n + col] = old[q2][cb] + acc[cb][q2];
         }
 }
 
@@ -1439,22 +1445,6 @@ k_cz_arn_gemv(const CoarseDesc* __restrict__ cd, int j, const double* __restrict
     }
 }
 
-// Second Gram-Schmidt pass: dots[chain*DS + b] = <v_b, u> for basis columns
-// b <= j.  One block per (b, chain).
-__global__ void k_cz_arn_dots(const CoarseDesc* __restrict__ cd, int j, const double* __restrict__ Vb,
-                              double* __restrict__ dots, int DS) {
-    __shared__ double sh[BAMG_BLK / BAMG_WAVE];
-    const CoarseDesc d = cd[blockIdx.y];
-    const int b = blockIdx.x;
-    if (j >= d.am || b > j) return;
-    const double* u = Vb + d.aoff + (size_t)(j + 1) * d.n;
-    const double* x = Vb + d.aoff + (size_t)b * d.n;
-    double s = 0;
-    for (int i = threadIdx.x; i < d.n; i += BAMG_BLK) s += x[i] * u[i];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) dots[(size_t)blockIdx.y * DS + b] = s;
-}
-
 // This block's sums of u^2 and u y (fixed order) into npart[(chain,
 // block) * 2 ..], for k_cz_arn_normalize.
 __device__ __forceinline__ void cz_norm_partials(double ss, double st, double* sh, double* sh2,
@@ -1516,27 +1506,126 @@ __global__ void k_cz_arn_update2(const CoarseDesc* __restrict__ cd, int j, const
     if (j < 0) cz_norm_partials(ss, st, sh, sh2, npart);    // the start vector goes to the norm next
 }
 
-// Second Gram-Schmidt pass: u -= sum_{b<=j} dots[b] v_b and H[0..j, j] +=
-// dots (H: chain stride HS, column-major ld am+1); npart as k_cz_arn_update2.
-__global__ void k_cz_arn_update(const CoarseDesc* __restrict__ cd, int j, const double* __restrict__ y,
-                                const double* __restrict__ dots, int DS, double* __restrict__ Vb,
-                                double* __restrict__ H, int HS, double* __restrict__ npart) {
-    __shared__ double sh[BAMG_BLK / BAMG_WAVE], sh2[BAMG_BLK / BAMG_WAVE];
+// Steps j >= 0 after the dots pass k_cz_arn_dots2, with K >= j + 1 (a
+// multiple of 8) accumulators: every thread loads v_0 .. v_{K-1} of its row
+// together (b > j re-reads v_j with a zero coefficient).
+//   k_cz_arn_update2p: the update of k_cz_arn_update2 (u <- u - a y -
+//     sum cf_b v_b in place, H[0..j, j] += cf) and this block's sums of the
+//     second Gram-Schmidt pass <v_b, u> (b <= j) into
+//     apart[((chain DS) + b) G + block] (G blocks per chain);
+//   k_cz_arn_updatep: dt_b = the G sums of b in block order, u - sum dt_b v_b
+//     into ub (the vector pool), H[0..j, j] += dt, the norm partials;
+//   k_cz_arn_normtv: v_{j+1} = u / ||u|| into the basis, H[j+1, j], vy, and
+//     w = T v_{j+1} for the next step (the neighbours' entries divided the same
+//     way; reading ub keeps them stable while the basis column is written).
+template <int K>
+__global__ void __launch_bounds__(BAMG_BLK)
+k_cz_arn_update2p(const CoarseDesc* __restrict__ cd, int j, const double* __restrict__ y,
+                  const double* __restrict__ cy, const double* __restrict__ dots, const double* __restrict__ vy,
+                  int DS, double* __restrict__ Vb, double* __restrict__ H, int HS, double* __restrict__ apart) {
+    __shared__ double cf[K];
+    __shared__ double red[(BAMG_BLK / BAMG_WAVE) * (GsRed<K>::KR + 2)];
     const CoarseDesc d = cd[blockIdx.y];
     if (j >= d.am) return;
     const double* dt = dots + (size_t)blockIdx.y * DS;
+    const double a = dt[0] / cy[blockIdx.y];
+    for (int b = threadIdx.x; b < K; b += BAMG_BLK) cf[b] = b <= j ? dt[1 + b] - a * vy[(size_t)blockIdx.y * DS + b] : 0.0;
+    __syncthreads();
+    const double* V = Vb + d.aoff;
     double* u = Vb + d.aoff + (size_t)(j + 1) * d.n;
+    double acc[K];
+#pragma unroll
+    for (int b = 0; b < K; ++b) acc[b] = 0.0;
+    for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < d.n; i += gridDim.x * BAMG_BLK) {
+        double q[K];
+#pragma unroll
+        for (int b = 0; b < K; ++b) q[b] = V[(size_t)min(b, j) * d.n + i];
+        const double yi = y[d.voff + i];
+        double s = u[i];
+        __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the products
+        s -= yi * a;
+#pragma unroll
+        for (int b = 0; b < K; ++b) s -= cf[b] * q[b];
+        u[i] = s;
+#pragma unroll
+        for (int b = 0; b < K; ++b) acc[b] += q[b] * s;
+    }
+    if (blockIdx.x == 0 && (int)threadIdx.x <= j)
+        H[(size_t)blockIdx.y * HS + (size_t)j * (d.am + 1) + threadIdx.x] += cf[threadIdx.x];
+    gs_store_partials<K>(acc, 0.0, 0.0, j + 1, apart, DS, red);
+}
+
+template <int K>
+__global__ void __launch_bounds__(BAMG_BLK)
+k_cz_arn_updatep(const CoarseDesc* __restrict__ cd, int j, const double* __restrict__ y,
+                 const double* __restrict__ apart, int DS, const double* __restrict__ Vb, double* __restrict__ H,
+                 int HS, double* __restrict__ ub, double* __restrict__ npart) {
+    __shared__ double dt[K];
+    __shared__ double sh[BAMG_BLK / BAMG_WAVE], sh2[BAMG_BLK / BAMG_WAVE];
+    const CoarseDesc d = cd[blockIdx.y];
+    if (j >= d.am) return;
+    const int G = gridDim.x;
+    for (int b = threadIdx.x; b < K; b += BAMG_BLK) {
+        double s = 0;
+        if (b <= j)
+            for (int g = 0; g < G; ++g) s += apart[((size_t)blockIdx.y * DS + b) * G + g];
+        dt[b] = s;
+    }
+    __syncthreads();
+    const double* V = Vb + d.aoff;
+    const double* u = Vb + d.aoff + (size_t)(j + 1) * d.n;
     double ss = 0, st = 0;
     for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < d.n; i += gridDim.x * BAMG_BLK) {
+        double q[K];
+#pragma unroll
+        for (int b = 0; b < K; ++b) q[b] = V[(size_t)min(b, j) * d.n + i];
+        const double yi = y[d.voff + i];
         double s = u[i];
-        for (int b = 0; b <= j; ++b) s -= dt[b] * Vb[d.aoff + (size_t)b * d.n + i];
-        u[i] = s;
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int b = 0; b < K; ++b) s -= dt[b] * q[b];
+        ub[d.voff + i] = s;
         ss += s * s;
-        st += s * y[d.voff + i];
+        st += s * yi;
     }
     if (blockIdx.x == 0 && (int)threadIdx.x <= j)
         H[(size_t)blockIdx.y * HS + (size_t)j * (d.am + 1) + threadIdx.x] += dt[threadIdx.x];
     cz_norm_partials(ss, st, sh, sh2, npart);
+}
+
+template <typename M>
+__global__ void k_cz_arn_normtv(const CoarseDesc* __restrict__ cd, int j, const double* __restrict__ ub,
+                                double* __restrict__ Vb, double* __restrict__ H, int HS, double* __restrict__ vy,
+                                int DS, const double* __restrict__ npart, double* __restrict__ w) {
+    const CoarseDesc d = cd[blockIdx.y];
+    if (j >= d.am) return;
+    const double* pp = npart + (size_t)blockIdx.y * gridDim.x * 2;
+    double s = 0, t = 0;
+    for (int q = 0; q < (int)gridDim.x; ++q) { s += pp[2 * q]; t += pp[2 * q + 1]; }
+    const double nrm = sqrt(s);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        H[(size_t)blockIdx.y * HS + (size_t)j * (d.am + 1) + j + 1] = nrm;
+        vy[(size_t)blockIdx.y * DS + j + 1] = nrm > 0 ? t / nrm : 0.0;
+    }
+    const double* u = ub + d.voff;
+    double* v = Vb + d.aoff + (size_t)(j + 1) * d.n;
+    for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < d.n; i += gridDim.x * BAMG_BLK) {
+        const double vi = nrm > 0 ? u[i] / nrm : 0.0;
+        v[i] = vi;
+        double tvs;
+        if (!d.trp) {
+            tvs = vi;
+        } else {
+            const M* tv = (const M*)d.tv;
+            tvs = 0;
+            const int gi = d.row0 + i;
+            for (int p = d.trp[gi]; p < d.trp[gi + 1]; ++p) {
+                const int col = d.tci[p] - d.row0;
+                tvs += (double)tv[p] * (nrm > 0 ? u[col] / nrm : 0.0);
+            }
+        }
+        w[d.voff + i] = tvs;
+    }
 }
 
 // Normalise basis column j+1 (or column 0 with j = -1): v = u / ||u||,

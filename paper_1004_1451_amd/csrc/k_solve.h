@@ -276,38 +276,6 @@ __global__ void k_seg_reduce_final(const ChainGeo* __restrict__ geo, int seg_row
 #define GS_MAXB 64
 #define GS_CS (2 * GS_MAXB + 4)
 
-template <int K>
-__device__ __forceinline__ void gs_store_partials(double (&acc_k)[K], double ey, double ex, int nb,
-                                                  double* __restrict__ part, int NDM, double* red) {
-    // the lane reduction runs on the next power of two (8 .. 64) of K, so a
-    // dot's summation order depends only on that power, not on K itself
-    constexpr int KR = K <= 8 ? 8 : K <= 16 ? 16 : K <= 32 ? 32 : 64;
-    constexpr int SH = KR >= 64 ? 0 : KR >= 32 ? 1 : KR >= 16 ? 2 : 3;
-    static_assert((BAMG_WAVE >> SH) == KR && K <= KR, "K must be at most 64");
-    double acc[KR];
-#pragma unroll
-    for (int b = 0; b < KR; ++b) acc[b] = b < K ? acc_k[b] : 0.0;
-    const int lane = threadIdx.x % BAMG_WAVE, wv = threadIdx.x / BAMG_WAVE;
-    wave_sum_many<KR>(acc);
-    ey = wave_sum(ey);
-    ex = wave_sum(ex);
-    if ((lane & ((1 << SH) - 1)) == 0) red[wv * (KR + 2) + (lane >> SH)] = acc[0];
-    if (lane == 0) { red[wv * (KR + 2) + KR] = ey; red[wv * (KR + 2) + KR + 1] = ex; }
-    __syncthreads();
-    const int t = threadIdx.x;
-    if (t < nb + 2) {
-        const int src = t < nb ? t : KR + (t - nb);
-        double v = 0;
-#pragma unroll
-        for (int q = 0; q < BAMG_BLK / BAMG_WAVE; ++q) v += red[q * (KR + 2) + src];
-        part[((size_t)blockIdx.y * NDM + t) * gridDim.x + blockIdx.x] = v;
-    }
-}
-
-// Reduction scratch of the passes (per wave: the KR + 2 sums of a row block).
-template <int K>
-struct GsRed { static constexpr int KR = K <= 8 ? 8 : K <= 16 ? 16 : K <= 32 ? 32 : 64; };
-
 // Dots pass: <q_b, w> (b < nb), <v_nb, w>, <w, w> on a chunk of one chain.
 // K >= nb accumulators per thread (K a multiple of 8); grid (chunks, chains).
 // V_b starts at V + b ldv.  Every thread issues all K loads of a row
