@@ -812,6 +812,81 @@ struct LsPoint {
     int valid, J;         // slot masks: non-empty, selected
 };
 
+// Weighted Gram G (lower triangle), right-hand side b and sigma of an F point
+// over its first NS slots (the others contribute zero), test vectors in the
+// order k = 0 .. R-1 (U columns, then V).
+template <typename T, int NS>
+__device__ __forceinline__ void ls_gram(int i, LsPoint& P, int valid, int Ru, int Rv, int VS, const T* __restrict__ U,
+                                        const T* __restrict__ V, const double* __restrict__ w, double& sigma) {
+    for (int part = 0; part < 2; ++part) {
+        const T* Xp = part == 0 ? U : V;
+        const int ld = part == 0 ? Ru : VS;
+        const int nk = part == 0 ? Ru : Rv;
+        const double* wp = w + (part == 0 ? 0 : Ru);
+        auto accumulate = [&](double wk, double xi, const double (&xs)[NS]) {
+            sigma += wk * xi * xi;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                double ws = wk * xs[s];
+                P.b[s] += ws * xi;
+#pragma unroll
+                for (int t = 0; t <= s; ++t) P.G[s][t] += ws * xs[t];
+            }
+        };
+        if (ld % 4 == 0) {
+            // four columns per 16-byte load (rows are 4-aligned), CH columns
+            // of the point's and its slots' rows loaded together before their
+            // sums; same order
+            constexpr int CH = sizeof(T) == 4 ? 12 : 8;
+            for (int k0 = 0; k0 < nk; k0 += CH) {
+                T xi[CH], xs4[NS][CH];
+                double wk[CH];
+#pragma unroll
+                for (int q = 0; q < CH; ++q) wk[q] = k0 + q < nk ? wp[k0 + q] : 0.0;
+                // every slot's row is loaded (an empty slot points at the
+                // point's own row, and columns past nk at the row's first
+                // four) and masked afterwards, so that no load waits behind a
+                // branch
+#pragma unroll
+                for (int q4 = 0; q4 < CH; q4 += 4) {
+                    const int kc = k0 + q4 < nk ? k0 + q4 : 0;
+                    T t4[4];
+                    VecIO<T, 4>::ld(Xp + (size_t)i * ld + kc, t4);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) xi[q4 + q] = t4[q];
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) {
+                        VecIO<T, 4>::ld(Xp + (size_t)P.sf[s] * ld + kc, t4);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) xs4[s][q4 + q] = t4[q];
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the sums
+#pragma unroll
+                for (int q = 0; q < CH; ++q) {
+                    if (k0 + q < nk) {
+                        double xs[NS];
+#pragma unroll
+                        for (int s = 0; s < NS; ++s) xs[s] = ((valid >> s) & 1) ? (double)xs4[s][q] : 0.0;
+                        accumulate(wk[q], (double)xi[q], xs);
+                    }
+                }
+            }
+        } else {
+#pragma unroll 2
+            for (int kk = 0; kk < nk; ++kk) {
+                double xs[NS];
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const double v = (double)Xp[(size_t)P.sf[s] * ld + kk];
+                    xs[s] = ((valid >> s) & 1) ? v : 0.0;
+                }
+                accumulate(wp[kk], (double)Xp[(size_t)i * ld + kk], xs);
+            }
+        }
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void ls_point(int i, const ChainGeo& g, int ia, int ib, int Ru, int Rv, int VS,
                                          const T* __restrict__ U, const T* __restrict__ V,
@@ -856,53 +931,11 @@ __device__ __forceinline__ void ls_point(int i, const ChainGeo& g, int ia, int i
 #pragma unroll
         for (int t = 0; t < 4; ++t) P.G[s][t] = 0;
     }
-    // U columns, then V columns (test vectors in a fixed order k = 0..R-1)
-    for (int part = 0; part < 2; ++part) {
-        const T* Xp = part == 0 ? U : V;
-        const int ld = part == 0 ? Ru : VS;
-        const int nk = part == 0 ? Ru : Rv;
-        const double* wp = w + (part == 0 ? 0 : Ru);
-        auto accumulate = [&](double wk, double xi, const double (&xs)[4]) {
-            sigma += wk * xi * xi;
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                double ws = wk * xs[s];
-                P.b[s] += ws * xi;
-#pragma unroll
-                for (int t = 0; t <= s; ++t) P.G[s][t] += ws * xs[t];
-            }
-        };
-        if (ld % 4 == 0) {
-            // four columns per 16-byte load (rows are 4-aligned); same order
-            for (int k0 = 0; k0 < nk; k0 += 4) {
-                T xi4[4], xs4[4][4];
-                VecIO<T, 4>::ld(Xp + (size_t)i * ld + k0, xi4);
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    if ((valid >> s) & 1) VecIO<T, 4>::ld(Xp + (size_t)P.sf[s] * ld + k0, xs4[s]);
-                    else
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) xs4[s][q] = (T)0;
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (k0 + q >= nk) break;
-                    double xs[4];
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) xs[s] = (double)xs4[s][q];
-                    accumulate(wp[k0 + q], (double)xi4[q], xs);
-                }
-            }
-        } else {
-#pragma unroll 2
-            for (int kk = 0; kk < nk; ++kk) {
-                double xs[4];
-#pragma unroll
-                for (int s = 0; s < 4; ++s) xs[s] = ((valid >> s) & 1) ? (double)Xp[(size_t)P.sf[s] * ld + kk] : 0.0;
-                accumulate(wp[kk], (double)Xp[(size_t)i * ld + kk], xs);
-            }
-        }
-    }
+    // U columns, then V columns (test vectors in a fixed order k = 0..R-1);
+    // points with at most two slots (slots 0 and 1) take a narrower copy of
+    // the same sums (the others' entries stay zero, as they would be)
+    if (ns <= 2) ls_gram<T, 2>(i, P, valid, Ru, Rv, VS, U, V, w, sigma);
+    else ls_gram<T, 4>(i, P, valid, Ru, Rv, VS, U, V, w, sigma);
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -1002,13 +1035,16 @@ __device__ __forceinline__ void ls_point(int i, const ChainGeo& g, int ia, int i
 }
 
 // Row i of P from weights p on the slots in mask J, in ascending coarse column;
-// returns the number of entries.
+// returns the number of entries.  The row is assembled in registers and
+// stored as one 16-byte column vector and one value vector.
 template <typename MP>
 __device__ __forceinline__ int write_prow(int i, int J, const int sc[4], const double p[4], int* __restrict__ pc,
                                           MP* __restrict__ pv) {
     int cnt = 0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) cnt += (J >> s) & 1;
+    int col[4] = {-1, -1, -1, -1};
+    MP val[4] = {(MP)0, (MP)0, (MP)0, (MP)0};
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         if (!((J >> s) & 1)) continue;
@@ -1016,10 +1052,12 @@ __device__ __forceinline__ int write_prow(int i, int J, const int sc[4], const d
 #pragma unroll
         for (int t = 0; t < 4; ++t)
             if (((J >> t) & 1) && (sc[t] < sc[s])) ++rank;
-        pc[(size_t)i * 4 + rank] = sc[s];
-        pv[(size_t)i * 4 + rank] = (MP)p[s];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q == rank) { col[q] = sc[s]; val[q] = (MP)p[s]; }
     }
-    for (int s = cnt; s < 4; ++s) { pc[(size_t)i * 4 + s] = -1; pv[(size_t)i * 4 + s] = (MP)0; }
+    *(int4*)(pc + (size_t)i * 4) = make_int4(col[0], col[1], col[2], col[3]);
+    VecIO<MP, 4>::st(pv + (size_t)i * 4, val);
     return cnt;
 }
 
@@ -1079,23 +1117,33 @@ k_ls_fit(int n, const ChainGeo* __restrict__ geo, int nch, int Ru, int use_v, co
     if (t >= n) return;
     const int ch = find_chain(geo, nch, t);
     const ChainGeo g = geo[ch];
-    // Thread t takes a point of its own grid row: on rows with C points
-    // (even ia) the odd columns (F points) come first and the even ones (C
-    // points) after them, so a wavefront's lanes mostly take the same branch.
+    // Thread t takes a point of its own grid row: the fine columns first,
+    // then the coarse ones, so a wavefront's lanes mostly take the same
+    // branch (rows with C points: F points, then C points; the other rows:
+    // F points with four slots, then those with two).
     const int lt = t - g.off;
     const int ia = (int)g.dy.div((uint32_t)lt), kk = lt - ia * g.ny;
     const bool rowc = grid_cpos(ia, g.nx, g.periodic);
     const int nf = grid_fine_count(g.ny, g.periodic);
-    const int ib = !rowc ? kk : (kk < nf ? 2 * kk + 1 : grid_fine_pos(kk - nf, g.ny, g.periodic));
+    const int ib = kk < nf ? 2 * kk + 1 : grid_fine_pos(kk - nf, g.ny, g.periodic);
     const int li = ia * g.ny + ib;
     const int i = g.off + li;
     if (rowc && grid_cpos(ib, g.ny, g.periodic)) {
         int I = g.coff + ((ia + 1) >> 1) * g.ncy + ((ib + 1) >> 1);
-        pc[(size_t)i * 4] = I; pv[(size_t)i * 4] = (MP)1;
-#pragma unroll
-        for (int s = 1; s < 4; ++s) { pc[(size_t)i * 4 + s] = -1; pv[(size_t)i * 4 + s] = (MP)0; }
-        if (inject)
-            for (int k = 0; k < Ru; ++k) inject[(size_t)I * Ru + k] = U[(size_t)i * Ru + k];
+        *(int4*)(pc + (size_t)i * 4) = make_int4(I, -1, -1, -1);
+        const MP one[4] = {(MP)1, (MP)0, (MP)0, (MP)0};
+        VecIO<MP, 4>::st(pv + (size_t)i * 4, one);
+        if (inject) {
+            if (Ru % 4 == 0) {
+                for (int k = 0; k < Ru; k += 4) {
+                    T x4[4];
+                    VecIO<T, 4>::ld(U + (size_t)i * Ru + k, x4);
+                    VecIO<T, 4>::st(inject + (size_t)I * Ru + k, x4);
+                }
+            } else {
+                for (int k = 0; k < Ru; ++k) inject[(size_t)I * Ru + k] = U[(size_t)i * Ru + k];
+            }
+        }
         if (jcnt) jcnt[i] = 1;
         if (feat_out)
             for (int k = 0; k < 24; ++k) feat_out[(size_t)i * 24 + k] = 0.0f;
@@ -1133,29 +1181,42 @@ __global__ void k_build_q(int nc, const ChainGeo* __restrict__ geoc, const Chain
     const int lI = I - gc.off;
     int A = (int)gc.dy.div((uint32_t)lI), Bq = lI - A * gc.ny;
     int fa = grid_fine_pos(A, g.nx, g.periodic), fb = grid_fine_pos(Bq, g.ny, g.periodic);
-    int fi[9];
-    double fv[9];
+    // the 3x3 fine box around I's fine position (empty entries: -1), then
+    // every box point's P columns as one 16-byte load each (an empty entry
+    // reloads the centre), all in flight together
+    int fb9[9];
 #pragma unroll
     for (int s = 0; s < 9; ++s) {
         int da = s / 3 - 1, db = s % 3 - 1;
         int na = fa + da, nb = fb + db;
-        fi[s] = -1; fv[s] = 0.0;
+        fb9[s] = -1;
         if (g.periodic) {
             na = na < 0 ? na + g.nx : (na >= g.nx ? na - g.nx : na);
             nb = nb < 0 ? nb + g.ny : (nb >= g.ny ? nb - g.ny : nb);
         } else if (na < 0 || na >= g.nx || nb < 0 || nb >= g.ny) {
             continue;
         }
-        int i = g.off + na * g.ny + nb;
+        fb9[s] = g.off + na * g.ny + nb;
+    }
+    int4 jc[9];
+#pragma unroll
+    for (int s = 0; s < 9; ++s) jc[s] = *(const int4*)(pc + (size_t)(fb9[s] >= 0 ? fb9[s] : fb9[4]) * 4);
+    int fi[9];
+    double fv[9];
+#pragma unroll
+    for (int s = 0; s < 9; ++s) {
+        fi[s] = -1; fv[s] = 0.0;
+        if (fb9[s] < 0) continue;
+        const int Js[4] = {jc[s].x, jc[s].y, jc[s].z, jc[s].w};
         int c = 0;
         bool hit = false;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            int J = pc[(size_t)i * 4 + t];
+            const int J = Js[t];
             c += J >= 0;
             hit |= J == I;
         }
-        if (hit) { fi[s] = i; fv[s] = 1.0 / c; }
+        if (hit) { fi[s] = fb9[s]; fv[s] = 1.0 / c; }
     }
     int cnt = 0;
 #pragma unroll
@@ -1203,15 +1264,14 @@ __device__ __forceinline__ unsigned gal_slot(int coff, int Ia, int Ib, int i, co
                                              const MV* __restrict__ ev, int eld, const int* __restrict__ pc,
                                              const MV* __restrict__ pv, MV* tmp) {
     unsigned mask = 0;
-    auto entry = [&](int j, MV mraw) {
+    // P row j: its columns and values as two 16-byte loads
+    auto load_p = [&](int j, int (&Js)[4], MV (&ps)[4]) {
+        const int4 jc = *(const int4*)(pc + (size_t)j * 4);
+        Js[0] = jc.x; Js[1] = jc.y; Js[2] = jc.z; Js[3] = jc.w;
+        if (VALS) VecIO<MV, 4>::ld(pv + (size_t)j * 4, ps);
+    };
+    auto apply = [&](MV mraw, const int (&Js)[4], const MV (&ps)[4]) {
         const MV m = VALS ? mraw : (MV)1;
-        int Js[4];
-        MV ps[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            Js[t] = pc[(size_t)j * 4 + t];
-            if (VALS) ps[t] = pv[(size_t)j * 4 + t];
-        }
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             if (Js[t] < 0) continue;
@@ -1224,9 +1284,37 @@ __device__ __forceinline__ unsigned gal_slot(int coff, int Ia, int Ib, int i, co
             }
         }
     };
-    if (!mrp) entry(i, (MV)1);
-    else if constexpr (VALS) row_entries<EF, MV>(i, mrp, mci, mv, eci, ev, eld, entry);
-    else row_cols<EF>(i, mrp, mci, eci, eld, [&](int j) { entry(j, (MV)1); });
+    if (!mrp) {
+        int Js[4];
+        MV ps[4];
+        load_p(i, Js, ps);
+        apply((MV)1, Js, ps);
+    } else if constexpr (EF == EF_ELL4) {
+        // the row's four entries, then their P rows, all loads of a stage in
+        // flight together, then the sums in entry order (on ELL-9 rows the
+        // nine P rows at once were measured slower than one after another)
+        constexpr int K = 4;
+        int c[K];
+        MV w[K];
+        const int4 c4 = *(const int4*)(eci + (size_t)i * 4);
+        c[0] = c4.x; c[1] = c4.y; c[2] = c4.z; c[3] = c4.w;
+        if (VALS) Ell4Val<MV>::ld(ev + (size_t)i * 4, w);
+        int Js[K][4];
+        MV ps[K][4];
+#pragma unroll
+        for (int k = 0; k < K; ++k) load_p(c[k], Js[k], ps[k]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) apply(VALS ? w[k] : (MV)1, Js[k], ps[k]);
+    } else {
+        auto entry = [&](int j, MV mraw) {
+            int Js[4];
+            MV ps[4];
+            load_p(j, Js, ps);
+            apply(mraw, Js, ps);
+        };
+        if constexpr (VALS) row_entries<EF, MV>(i, mrp, mci, mv, eci, ev, eld, entry);
+        else row_cols<EF>(i, mrp, mci, eci, eld, [&](int j) { entry(j, (MV)1); });
+    }
     return mask;
 }
 
