@@ -768,7 +768,7 @@ struct Engine : bamg_ctx {
     // Coarsest descriptors (chain c's coarsest level is its last plan entry)
     // and the pools of the coarsest pseudo-inverse and eigensolve.
     void alloc_coarsest() {
-        long long woff = 0, boff = 0, aoff = 0;
+        long long woff = 0, boff = 0, aoff = 0, wfoff = 0;
         int voff = 0;
         AMmax = 0; maxnL = 0; nxmax = 0;
         dense_fallback = false;
@@ -798,6 +798,9 @@ struct Engine : bamg_ctx {
             d.bord = 0;
             d.boff = boff;
             d.aoff = aoff;
+            d.wfld = (d.n + 3) & ~3;
+            d.wfoff = wfoff;
+            wfoff += (long long)d.n * d.wfld;
             d.am = (o.n_eig > 1) ? std::max(0, std::min({o.arnoldi_m, d.n - 1, HQR_MAXM})) : 0;
             d.brp = L[lc].B.rp; d.bci = L[lc].B.ci; d.bv = L[lc].B.v;
             d.trp = L[lc].Tm.rp; d.tci = L[lc].Tm.ci; d.tv = L[lc].Tm.v;
@@ -830,7 +833,7 @@ struct Engine : bamg_ctx {
         }
         cds = A.upload(cdsh);
         Wp = A.alloc<double>(wall);
-        if (MIXED) Wfp = A.alloc<float>(woff);
+        if (MIXED) Wfp = A.alloc<float>(std::max<long long>(wfoff, 1));
         Fp = A.alloc<double>(std::max<long long>(boff, 1));
         for (double** p : {&ypool, &cpool, &bcolp, &t1, &t2, &rre, &rim}) *p = A.alloc<double>(NVt);
         gtpart = A.alloc<double>((size_t)ceil_div(maxnL, GT_RCH) * NVt);
@@ -1296,7 +1299,9 @@ struct Engine : bamg_ctx {
         for (double v : mp) mn = std::min(mn, v);
         st.coarsest_min_pivot = mn;
         if (!(mn > 1e-12)) fail(BAMG_ESINGULAR, "coarsest pivot %.3e below 1e-12 of max |B_L|", mn);
-        if (MIXED) LAUNCH((k_cast<double, float>), nblk(wtot), BAMG_BLK, s, wtot, (const double*)Wp, Wfp);
+        if (MIXED)
+            hipLaunchKernelGGL(k_cz_w_f32, dim3(std::min(2048, nblk((long long)maxnL * maxnL)), nch), dim3(BAMG_BLK), 0,
+                               s, (const CoarseDesc*)cd, (const double*)Wp, Wfp);
     }
 
     // The coarsest inverse of a bordered grid from the main part's inverse

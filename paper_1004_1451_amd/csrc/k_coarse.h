@@ -30,6 +30,8 @@ struct CoarseDesc {
     long long woff;           // offset of its n x n block in the W pool
     long long boff;           // offset of its block-LU factors (5 * nx * ny^2)
     long long aoff;           // offset of its Arnoldi basis (n * (am + 1))
+    long long wfoff;          // offset of its FP32 copy of W (rows of wfld)
+    int wfld;                 // that copy's row length (n rounded up to 4)
     int am;                   // Arnoldi steps (0: no eigenpairs)
     FastDiv dy;
     const int* brp; const int* bci; const void* bv;   // CSR of B on that level
@@ -1229,6 +1231,18 @@ k_cz_gemv(const CoarseDesc* __restrict__ cd, int which, const double* __restrict
     }
 }
 
+// FP32 copy of every chain's W for the mixed-precision cycle, rows padded
+// with zeros to wfld columns (grid (blocks, chains)).
+__global__ void k_cz_w_f32(const CoarseDesc* __restrict__ cd, const double* __restrict__ Wp,
+                           float* __restrict__ Wf) {
+    const CoarseDesc d = cd[blockIdx.y];
+    const int ld = d.wfld, tot = d.n * ld;
+    for (int e = blockIdx.x * BAMG_BLK + threadIdx.x; e < tot; e += gridDim.x * BAMG_BLK) {
+        const int r = e / ld, c = e - r * ld;
+        Wf[d.wfoff + e] = c < d.n ? (float)Wp[d.woff + (size_t)r * d.n + c] : 0.0f;
+    }
+}
+
 // FP32 copy of the same product for the mixed-precision cycle (vector in
 // the level's FP32 cycle buffer at row0).
 __global__ void __launch_bounds__(BAMG_BLK)
@@ -1236,17 +1250,18 @@ k_cz_gemv_f32(const CoarseDesc* __restrict__ cd, const float* __restrict__ Wp, c
               float* __restrict__ out, const int* __restrict__ act) {
     if (act && !act[blockIdx.y]) return;
     const CoarseDesc d = cd[blockIdx.y];
-    const float* W = Wp + d.woff;
+    const float* W = Wp + d.wfoff;
     const int lane = threadIdx.x % BAMG_WAVE;
     // Lane L sums the column groups 4j .. 4j+3, j = L, L + 64, ..., in column
-    // order, then tail column 4 (n / 4) + L; with 16-byte aligned rows and
-    // vector each group is one 16-byte load, otherwise four scalar loads in
-    // the same order (so the sum does not depend on the alignment).
+    // order, then tail column 4 (n / 4) + L; with 16-byte aligned rows (the
+    // copy's rows are padded to a multiple of 4) and vector each group is one
+    // 16-byte load, otherwise four scalar loads in the same order (so the sum
+    // does not depend on the alignment).
     const int n4 = d.n / 4;
-    const bool v4 = (d.n & 3) == 0 && (d.row0 & 3) == 0 && (d.woff & 3) == 0;
+    const bool v4 = (d.wfld & 3) == 0 && (d.row0 & 3) == 0 && (d.wfoff & 3) == 0;
     for (int row = blockIdx.x * (BAMG_BLK / BAMG_WAVE) + threadIdx.x / BAMG_WAVE; row < d.n;
          row += gridDim.x * (BAMG_BLK / BAMG_WAVE)) {
-        const float* a = W + (size_t)row * d.n;
+        const float* a = W + (size_t)row * d.wfld;
         const float* xr = x + d.row0;
         float s = 0;
         if (v4) {
@@ -1265,8 +1280,8 @@ k_cz_gemv_f32(const CoarseDesc* __restrict__ cd, const float* __restrict__ Wp, c
             for (int j = lane; j < n4; j += BAMG_WAVE)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) s += a[4 * j + q] * xr[4 * j + q];
-            if (4 * n4 + lane < d.n) s += a[4 * n4 + lane] * xr[4 * n4 + lane];
         }
+        if (4 * n4 + lane < d.n) s += a[4 * n4 + lane] * xr[4 * n4 + lane];
         s = wave_sum(s);
         if (lane == 0) out[d.row0 + row] = s;
     }

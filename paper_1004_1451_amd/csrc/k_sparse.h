@@ -632,6 +632,23 @@ __device__ __forceinline__ void row_entries(int i, const int* __restrict__ rp, c
     }
 }
 
+// The stored entries of an ELL row as arrays (K = 4 for ELL-4, 9 for
+// ELL-9; 0: CSR, not handled here), in row_entries' order.
+template <int EF>
+struct RowK { static constexpr int K = EF == EF_ELL4 ? 4 : EF == EF_ELL9 ? 9 : 0; };
+template <int EF, typename M, int K>
+__device__ __forceinline__ void row_load(int i, const int* __restrict__ eci, const M* __restrict__ ev, int eld,
+                                         int (&c)[K], M (&w)[K]) {
+    if constexpr (EF == EF_ELL4) {
+        const int4 c4 = *(const int4*)(eci + (size_t)i * 4);
+        c[0] = c4.x; c[1] = c4.y; c[2] = c4.z; c[3] = c4.w;
+        Ell4Val<M>::ld(ev + (size_t)i * 4, w);
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) { c[k] = eci[(size_t)k * eld + i]; w[k] = ev[(size_t)k * eld + i]; }
+    }
+}
+
 // The columns only (for passes that need the pattern): f(column) for the
 // entries row_entries visits, in the same order.
 template <int EF, typename F>
@@ -685,23 +702,65 @@ k_colnorm_partial(const ChainGeo* __restrict__ geo, int seg_rows, int Ru, int us
 #pragma unroll
     for (int q = 0; q < VW; ++q) { ar[q] = 0.0; ax[q] = 0.0; }
     if (dr < rpp) {
-        for (int i = r0 + dr; i < r1; i += rpp) {
-            double acc[VW];
+        if constexpr (EF == EF_ELL4) {
+            // UR rows per round (i, i + rpp, ...): their entries, then every
+            // neighbour's and their own values, all loads of a stage in
+            // flight together; sums in the same row and entry order (on
+            // ELL-9 rows this was measured slower than row by row)
+            constexpr int K = RowK<EF>::K, UR = 4;
+            for (int i = r0 + dr; i < r1; i += UR * rpp) {
+                int cj[UR][K], ii[UR];
+                M wj[UR][K];
 #pragma unroll
-            for (int q = 0; q < VW; ++q) acc[q] = 0.0;
-            row_entries<EF, M>(i, rp, ci, v, eci, ev, eld, [&](int j, M bvj) {
-                const double b = (double)bvj;
-                T x[VW];
-                VecIO<T, VW>::ld(X + (size_t)j * ld + kx, x);
+                for (int u = 0; u < UR; ++u) {
+                    ii[u] = i + u * rpp < r1 ? i + u * rpp : i;
+                    row_load<EF, M, K>(ii[u], eci, ev, eld, cj[u], wj[u]);
+                }
+                T xj[UR][K][VW], xi[UR][VW];
 #pragma unroll
-                for (int q = 0; q < VW; ++q) acc[q] += b * (double)x[q];
-            });
-            T xi[VW];
-            VecIO<T, VW>::ld(X + (size_t)i * ld + kx, xi);
+                for (int u = 0; u < UR; ++u) {
 #pragma unroll
-            for (int q = 0; q < VW; ++q) {
-                ar[q] += acc[q] * acc[q];
-                ax[q] += (double)xi[q] * (double)xi[q];
+                    for (int k = 0; k < K; ++k) VecIO<T, VW>::ld(X + (size_t)cj[u][k] * ld + kx, xj[u][k]);
+                    VecIO<T, VW>::ld(X + (size_t)ii[u] * ld + kx, xi[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < UR; ++u) {
+                    if (i + u * rpp >= r1) continue;
+                    double acc[VW];
+#pragma unroll
+                    for (int q = 0; q < VW; ++q) acc[q] = 0.0;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const double b = (double)wj[u][k];
+#pragma unroll
+                        for (int q = 0; q < VW; ++q) acc[q] += b * (double)xj[u][k][q];
+                    }
+#pragma unroll
+                    for (int q = 0; q < VW; ++q) {
+                        ar[q] += acc[q] * acc[q];
+                        ax[q] += (double)xi[u][q] * (double)xi[u][q];
+                    }
+                }
+            }
+        } else {
+            for (int i = r0 + dr; i < r1; i += rpp) {
+                double acc[VW];
+#pragma unroll
+                for (int q = 0; q < VW; ++q) acc[q] = 0.0;
+                row_entries<EF, M>(i, rp, ci, v, eci, ev, eld, [&](int j, M bvj) {
+                    const double b = (double)bvj;
+                    T x[VW];
+                    VecIO<T, VW>::ld(X + (size_t)j * ld + kx, x);
+#pragma unroll
+                    for (int q = 0; q < VW; ++q) acc[q] += b * (double)x[q];
+                });
+                T xi[VW];
+                VecIO<T, VW>::ld(X + (size_t)i * ld + kx, xi);
+#pragma unroll
+                for (int q = 0; q < VW; ++q) {
+                    ar[q] += acc[q] * acc[q];
+                    ax[q] += (double)xi[q] * (double)xi[q];
+                }
             }
         }
     }
