@@ -1329,12 +1329,24 @@ __device__ __forceinline__ unsigned gal_slot(int coff, int Ia, int Ib, int i, co
         Js[0] = jc.x; Js[1] = jc.y; Js[2] = jc.z; Js[3] = jc.w;
         if (VALS) VecIO<MV, 4>::ld(pv + (size_t)j * 4, ps);
     };
+    // without wrap-around (and ncy >= 3) the box slot of coarse column J
+    // follows from J - (I - ncy - 1) = (da + 1) ncy + (db + 1), da, db in
+    // {-1, 0, 1}
+    const int sbase = coff + Ia * ncy + Ib - ncy - 1;
+    const bool general = periodic || ncy < 3;
     auto apply = [&](MV mraw, const int (&Js)[4], const MV (&ps)[4]) {
         const MV m = VALS ? mraw : (MV)1;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             if (Js[t] < 0) continue;
-            int sl = box_slot(Ia, Ib, Js[t] - coff, dcy, ncx, ncy, periodic);
+            int sl;
+            if (general) {
+                sl = box_slot(Ia, Ib, Js[t] - coff, dcy, ncx, ncy, periodic);
+            } else {
+                const int q = Js[t] - sbase;
+                const int dap = (q >= ncy ? 1 : 0) + (q >= 2 * ncy ? 1 : 0);
+                sl = dap * 3 + (q - dap * ncy);
+            }
             mask |= 1u << sl;
             if (VALS) {
                 MV c = m * ps[t];
@@ -1375,6 +1387,58 @@ __device__ __forceinline__ unsigned gal_slot(int coff, int Ia, int Ib, int i, co
         else row_cols<EF>(i, mrp, mci, eci, eld, [&](int j) { entry(j, (MV)1); });
     }
     return mask;
+}
+
+// The output stage of the Galerkin kernels (all GAL_THREADS threads of the
+// block call it): thread (lr, s) of coarse row I (valid when I < nc) brings its
+// slot sums tb / tt and box masks mb / mt; the nine threads of a row add the
+// sums per box slot in order s = 0..8 through LDS (sv, sm) and thread u writes
+// box slot u at its rank among the row's structural slots into the
+// column-major ELL-9 arrays of each product, the free slots padded with
+// (I, 0); *cnt[I] = structural slots of the row.
+template <typename MV>
+__device__ __forceinline__ void gal_write(int I, int nc, int lr, int s, int Ia, int Ib, int ncx, int ncy, int periodic,
+                                          int goff, const MV (&tb)[9], const MV (&tt)[9], unsigned mb, unsigned mt,
+                                          MV (*sv)[9], unsigned* sm, int* __restrict__ bcc, MV* __restrict__ bcv,
+                                          int* __restrict__ bcnt, int* __restrict__ tcc, MV* __restrict__ tcv,
+                                          int* __restrict__ tcnt) {
+    // the row's coarse columns of the nine box slots
+    int col[9];
+#pragma unroll
+    for (int w = 0; w < 9; ++w) {
+        int a = Ia + w / 3 - 1, b = Ib + w % 3 - 1;
+        if (periodic) {
+            a = a < 0 ? a + ncx : (a >= ncx ? a - ncx : a);
+            b = b < 0 ? b + ncy : (b >= ncy ? b - ncy : b);
+        }
+        col[w] = goff + a * ncy + b;
+    }
+    for (int prod = 0; prod < 2; ++prod) {
+        if (prod) __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 9; ++u) sv[threadIdx.x][u] = prod ? tt[u] : tb[u];
+        sm[threadIdx.x] = prod ? mt : mb;
+        __syncthreads();
+        if (I < nc) {
+            int* cc = prod ? tcc : bcc;
+            MV* cv = prod ? tcv : bcv;
+            unsigned mask = 0;
+            for (int t = 0; t < 9; ++t) mask |= sm[lr * 9 + t];
+            const int u = s;
+            const int cnt = __popc(mask);
+            if ((mask >> u) & 1) {
+                MV acc = 0;
+                for (int t = 0; t < 9; ++t) acc += sv[lr * 9 + t][u];
+                int rank = 0;
+#pragma unroll
+                for (int t = 0; t < 9; ++t) rank += ((mask >> t) & 1) && (col[t] < col[u]);
+                cc[(size_t)rank * nc + I] = col[u];
+                cv[(size_t)rank * nc + I] = acc;
+            }
+            if (u >= cnt) { cc[(size_t)u * nc + I] = I; cv[(size_t)u * nc + I] = (MV)0; }
+            if (u == 0) (prod ? tcnt : bcnt)[I] = cnt;
+        }
+    }
 }
 
 // Both products of a grid level in one pass: B_{l+1} = Q (B_l P) and
@@ -1428,43 +1492,8 @@ k_galerkin_bt(int nc, const ChainGeo* __restrict__ geoc, int nch, const int* __r
             for (int u = 0; u < 9; ++u) { tb[u] = q * tb[u]; tt[u] = q * tt[u]; }
         }
     }
-    // the row's coarse columns of the nine box slots
-    int col[9];
-#pragma unroll
-    for (int w = 0; w < 9; ++w) {
-        int a = Ia + w / 3 - 1, b = Ib + w % 3 - 1;
-        if (periodic) {
-            a = a < 0 ? a + ncx : (a >= ncx ? a - ncx : a);
-            b = b < 0 ? b + ncy : (b >= ncy ? b - ncy : b);
-        }
-        col[w] = goff + a * ncy + b;
-    }
-    for (int prod = 0; prod < 2; ++prod) {
-        if (prod) __syncthreads();
-#pragma unroll
-        for (int u = 0; u < 9; ++u) sv[threadIdx.x][u] = prod ? tt[u] : tb[u];
-        sm[threadIdx.x] = prod ? mt : mb;
-        __syncthreads();
-        if (I < nc) {
-            int* cc = prod ? tcc : bcc;
-            MV* cv = prod ? tcv : bcv;
-            unsigned mask = 0;
-            for (int t = 0; t < 9; ++t) mask |= sm[lr * 9 + t];
-            const int u = s;
-            const int cnt = __popc(mask);
-            if ((mask >> u) & 1) {
-                MV acc = 0;
-                for (int t = 0; t < 9; ++t) acc += sv[lr * 9 + t][u];
-                int rank = 0;
-#pragma unroll
-                for (int t = 0; t < 9; ++t) rank += ((mask >> t) & 1) && (col[t] < col[u]);
-                cc[(size_t)rank * nc + I] = col[u];
-                cv[(size_t)rank * nc + I] = acc;
-            }
-            if (u >= cnt) { cc[(size_t)u * nc + I] = I; cv[(size_t)u * nc + I] = (MV)0; }
-            if (u == 0) (prod ? tcnt : bcnt)[I] = cnt;
-        }
-    }
+    gal_write<MV>(I, nc, lr, s, Ia, Ib, ncx, ncy, periodic, goff, tb, tt, mb, mt, sv, sm, bcc, bcv, bcnt, tcc, tcv,
+                  tcnt);
 }
 
 // CSR rows of both products from their ELL-9 copies (blockIdx.y: 0 = B,
