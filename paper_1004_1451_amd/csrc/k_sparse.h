@@ -99,15 +99,42 @@ __global__ void k_build_b(int n, const int* __restrict__ rp, const int* __restri
     int q = brp[i];
     bool done = false;
     double diag = 1.0;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) {
-        int j = ci[p];
-        if (!done && j > i) { bci[q] = i; bv[q] = 1.0; ++q; done = true; }
-        if (j == i) { diag = 1.0 - v[p]; bci[q] = i; bv[q] = diag; done = true; }
-        else { bci[q] = j; bv[q] = -v[p]; }
+    // each entry written once, to the FP64 and (if asked) the low-precision
+    // values together
+    auto put = [&](int col, double val) {
+        bci[q] = col;
+        bv[q] = val;
+        if (bv_lo) bv_lo[q] = (M)val;
         ++q;
+    };
+    const int p0 = rp[i], p1 = rp[i + 1];
+    if (p1 - p0 <= 4) {
+        // short rows: all loads of the row issued before the writes
+        int jj[4];
+        double vv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int pu = p0 + min(u, max(p1 - p0 - 1, 0));
+            jj[u] = p1 > p0 ? ci[pu] : 0;
+            vv[u] = p1 > p0 ? v[pu] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (u >= p1 - p0) break;
+            const int j = jj[u];
+            if (!done && j > i) { put(i, 1.0); done = true; }
+            if (j == i) { diag = 1.0 - vv[u]; put(i, diag); done = true; }
+            else put(j, -vv[u]);
+        }
+    } else {
+        for (int p = p0; p < p1; ++p) {
+            const int j = ci[p];
+            if (!done && j > i) { put(i, 1.0); done = true; }
+            if (j == i) { diag = 1.0 - v[p]; put(i, diag); done = true; }
+            else put(j, -v[p]);
+        }
     }
-    if (!done) { bci[q] = i; bv[q] = 1.0; }
-    if (bv_lo) for (int p = brp[i]; p < brp[i + 1]; ++p) bv_lo[p] = (M)bv[p];
+    if (!done) put(i, 1.0);
     if (!(diag > 0.0)) atomicOr(err, ERR_ZERODIAG);
     dinv[i] = omega / diag;
     if (dinv_lo) dinv_lo[i] = (M)(omega / diag);
