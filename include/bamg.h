@@ -174,7 +174,10 @@ typedef struct {
     int32_t n_levels;
     int32_t n_v;            /* columns of eigenvector approximations          */
     double op_complexity;   /* sum nnz(B_l) / nnz(B_0)                         */
-    double coarsest_min_pivot; /* min |pivot| / max |B_L entry| in the coarsest inverse */
+    double coarsest_min_pivot; /* smallest Gauss-Jordan pivot of the coarsest inverse:
+                                  diagonal blocks' pivots / max |B_L entry|; on
+                                  grids without the periodic arrow also the
+                                  joins' pivots of I - C G (dimensionless) */
     double t_setup_ms, t_solve_ms;   /* host wall clock of the last calls      */
     /* with options.profile: HIP-event time and launch count of the level-0
        test-vector sweeps (every launch), of the launch that forms both
