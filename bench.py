@@ -222,8 +222,9 @@ def _roofline(stats, traffic):
     st = stats[-1]
     return sweep_ms, {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                       "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                      "kernel": "%s<VW=%d,BS=%d> (level-0 test-vector sweep%s)" % (
+                      "kernel": "%s<VW=%d,BS=%d%s> (level-0 test-vector sweep%s)" % (
                           "k_sweep_ve" if st.sweep_ell else "k_sweep_v", st.sweep_vw, st.sweep_bs,
+                          ",RP=%d" % st.sweep_rp if st.sweep_ell else "",
                           ", ELL-4 copy of B_0" if st.sweep_ell else ""),
                       "bytes_per_launch": int(sweep_bytes), "mean_launch_us": round(sweep_ms * 1e3, 2)}
 

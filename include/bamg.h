@@ -193,7 +193,7 @@ typedef struct {
     int32_t sweep_vw, sweep_bs; /* launch shape of the level-0 multi-vector sweep:
                                    columns per thread, threads per workgroup
                                    (VW 1, 2, 3, 4, 6 or 12; autotuned once per shape and process;
-                                   BAMG_SWEEP_VARIANT="VW,BS" forces one)    */
+                                   BAMG_SWEEP_VARIANT="VW,BS[,RP]" forces one) */
     double tune_ms;         /* process total spent timing sweep candidates    */
     int64_t mlp_points;     /* learned form: F points judged (all levels)      */
     int64_t mlp_fallback;   /* of which fell back to the least-squares row     */
@@ -212,6 +212,8 @@ typedef struct {
     double gal_csr_ms, lsfit2_ms;
     int32_t gal_csr_launches, lsfit2_launches;
     int64_t gal_csr_bytes, lsfit2_bytes;
+    int32_t sweep_rp;       /* row pieces per thread of the level-0 sweep (1, or
+                               2 on the ELL-4 copy; autotuned with sweep_vw)  */
 } bamg_stats;
 
 typedef struct {

@@ -222,8 +222,9 @@ DeviceCache& device_cache() {
 // columns of a row, workgroups of BS threads.  Every variant computes the same
 // bits; the fastest for a (device, rows, R, nnz, type) shape is found once per
 // process by timing each candidate on the real operator, then reused.
-// BAMG_SWEEP_VARIANT="VW,BS" in the environment forces a variant.
-struct SweepShape { int vw = 1, bs = 256; };
+// On an ELL-4 operator a thread may also take two row pieces (rp = 2).
+// BAMG_SWEEP_VARIANT="VW,BS[,RP]" in the environment forces a variant.
+struct SweepShape { int vw = 1, bs = 256, rp = 1; };
 
 struct SweepTuner {
     std::mutex mu;
@@ -239,13 +240,15 @@ SweepTuner& sweep_tuner() {
 bool forced_sweep_shape(int R, SweepShape& out) {
     const char* e = getenv("BAMG_SWEEP_VARIANT");
     if (!e || !*e) return false;
-    int vw = 0, bs = 0;
-    if (sscanf(e, "%d,%d", &vw, &bs) != 2) return false;
+    int vw = 0, bs = 0, rp = 1;
+    if (sscanf(e, "%d,%d,%d", &vw, &bs, &rp) < 2) return false;
     if ((vw != 1 && vw != 2 && vw != 3 && vw != 4 && vw != 6 && vw != 12) || (bs != 128 && bs != 256 && bs != 512) ||
-        ((vw == 3 || vw > 4) && bs > 256) || R % vw)
+        ((vw == 3 || vw > 4) && bs > 256) || R % vw || (rp != 1 && rp != 2) ||
+        (rp == 2 && ((vw != 2 && vw != 4) || bs == 128)))
         return false;
     out.vw = vw;
     out.bs = bs;
+    out.rp = rp;
     return true;
 }
 
@@ -936,17 +939,20 @@ struct Engine : bamg_ctx {
 
     // -------------------------------------------------------------- setup steps
     // nu homogeneous sweeps on the continuing rows of level l (R columns).
-    template <int VW, int BS>
+    template <int VW, int BS, int RP = 1>
     void sweep_launch(int rows, int R, const Csr<T>& Bm, const T* dinv, const T* X, const T* F, T* Y) {
         const int G = R / VW;
         const long long tot = (long long)rows * G;
         const int grid = (int)std::max<long long>(1, (tot + BS - 1) / BS);
         if (Bm.eci) {
-            hipLaunchKernelGGL((k_sweep_ve<T, T, VW, BS>), dim3(grid), dim3(BS), 0, s, rows, G, FastDiv((uint32_t)G),
-                               (const int*)Bm.eci, (const T*)Bm.ev, dinv, X, F, Y);
+            const long long span = (tot + RP - 1) / RP;
+            hipLaunchKernelGGL((k_sweep_ve<T, T, VW, BS, RP>), dim3((int)std::max<long long>(1, (span + BS - 1) / BS)),
+                               dim3(BS), 0, s, rows, G, FastDiv((uint32_t)G), (const int*)Bm.eci, (const T*)Bm.ev,
+                               dinv, X, F, Y);
             HIPCHK(hipGetLastError());
             return;
         }
+        if (RP != 1) fail(BAMG_EDEVICE, "two row pieces per thread need the ELL-4 operator");
         if (Bm.cci) {
             hipLaunchKernelGGL((k_sweep_v9<T, T, VW, BS>), dim3(grid), dim3(BS), 0, s, rows, G, FastDiv((uint32_t)G),
                                Bm.cld, (const int*)Bm.cci, (const T*)Bm.cv, dinv, X, F, Y);
@@ -960,23 +966,27 @@ struct Engine : bamg_ctx {
 
     void sweep_shape(const SweepShape& sh, int rows, int R, const Csr<T>& Bm, const T* dinv, const T* X, const T* F,
                      T* Y) {
-        switch (sh.vw * 1000 + sh.bs) {
-            case 1128: sweep_launch<1, 128>(rows, R, Bm, dinv, X, F, Y); break;
-            case 1256: sweep_launch<1, 256>(rows, R, Bm, dinv, X, F, Y); break;
-            case 1512: sweep_launch<1, 512>(rows, R, Bm, dinv, X, F, Y); break;
-            case 2128: sweep_launch<2, 128>(rows, R, Bm, dinv, X, F, Y); break;
-            case 2256: sweep_launch<2, 256>(rows, R, Bm, dinv, X, F, Y); break;
-            case 2512: sweep_launch<2, 512>(rows, R, Bm, dinv, X, F, Y); break;
-            case 4128: sweep_launch<4, 128>(rows, R, Bm, dinv, X, F, Y); break;
-            case 4256: sweep_launch<4, 256>(rows, R, Bm, dinv, X, F, Y); break;
-            case 4512: sweep_launch<4, 512>(rows, R, Bm, dinv, X, F, Y); break;
-            case 3128: sweep_launch<3, 128>(rows, R, Bm, dinv, X, F, Y); break;
-            case 3256: sweep_launch<3, 256>(rows, R, Bm, dinv, X, F, Y); break;
-            case 6128: sweep_launch<6, 128>(rows, R, Bm, dinv, X, F, Y); break;
-            case 6256: sweep_launch<6, 256>(rows, R, Bm, dinv, X, F, Y); break;
-            case 12128: sweep_launch<12, 128>(rows, R, Bm, dinv, X, F, Y); break;
-            case 12256: sweep_launch<12, 256>(rows, R, Bm, dinv, X, F, Y); break;
-            default: fail(BAMG_EDEVICE, "no sweep variant %d,%d", sh.vw, sh.bs);
+        switch (sh.rp * 100000 + sh.vw * 1000 + sh.bs) {
+            case 202256: sweep_launch<2, 256, 2>(rows, R, Bm, dinv, X, F, Y); break;
+            case 202512: sweep_launch<2, 512, 2>(rows, R, Bm, dinv, X, F, Y); break;
+            case 204256: sweep_launch<4, 256, 2>(rows, R, Bm, dinv, X, F, Y); break;
+            case 204512: sweep_launch<4, 512, 2>(rows, R, Bm, dinv, X, F, Y); break;
+            case 101128: sweep_launch<1, 128>(rows, R, Bm, dinv, X, F, Y); break;
+            case 101256: sweep_launch<1, 256>(rows, R, Bm, dinv, X, F, Y); break;
+            case 101512: sweep_launch<1, 512>(rows, R, Bm, dinv, X, F, Y); break;
+            case 102128: sweep_launch<2, 128>(rows, R, Bm, dinv, X, F, Y); break;
+            case 102256: sweep_launch<2, 256>(rows, R, Bm, dinv, X, F, Y); break;
+            case 102512: sweep_launch<2, 512>(rows, R, Bm, dinv, X, F, Y); break;
+            case 104128: sweep_launch<4, 128>(rows, R, Bm, dinv, X, F, Y); break;
+            case 104256: sweep_launch<4, 256>(rows, R, Bm, dinv, X, F, Y); break;
+            case 104512: sweep_launch<4, 512>(rows, R, Bm, dinv, X, F, Y); break;
+            case 103128: sweep_launch<3, 128>(rows, R, Bm, dinv, X, F, Y); break;
+            case 103256: sweep_launch<3, 256>(rows, R, Bm, dinv, X, F, Y); break;
+            case 106128: sweep_launch<6, 128>(rows, R, Bm, dinv, X, F, Y); break;
+            case 106256: sweep_launch<6, 256>(rows, R, Bm, dinv, X, F, Y); break;
+            case 112128: sweep_launch<12, 128>(rows, R, Bm, dinv, X, F, Y); break;
+            case 112256: sweep_launch<12, 256>(rows, R, Bm, dinv, X, F, Y); break;
+            default: fail(BAMG_EDEVICE, "no sweep variant %d,%d,%d", sh.vw, sh.bs, sh.rp);
         }
     }
 
@@ -985,7 +995,10 @@ struct Engine : bamg_ctx {
     // 2^20 entries are not worth timing and take the plain layout.
     SweepShape pick_sweep_shape(int l, int R, const T* X, T* scratch) {
         SweepShape sh;
-        if (forced_sweep_shape(R, sh)) return sh;
+        if (forced_sweep_shape(R, sh)) {
+            if (!L[l].B.eci) sh.rp = 1;        // two pieces per thread only on the ELL-4 operator
+            return sh;
+        }
         auto& lv = L[l];
         const int rows = lv.cont_rows;
         if ((long long)rows * R < (1LL << 20)) return sh;
@@ -1005,21 +1018,26 @@ struct Engine : bamg_ctx {
         std::vector<SweepShape> cand;
         for (int vw : {1, 2, 3, 4, 6, 12})
             for (int bs : {128, 256, 512})
-                if (R % vw == 0 && (vw == 1 || vw == 2 || vw == 4 || bs <= 256)) cand.push_back({vw, bs});
+                if (R % vw == 0 && (vw == 1 || vw == 2 || vw == 4 || bs <= 256)) cand.push_back({vw, bs, 1});
+        if (lv.B.eci)
+            for (int vw : {2, 4})
+                for (int bs : {256, 512})
+                    if (R % vw == 0) cand.push_back({vw, bs, 2});
         hipEvent_t a, b;
         a = event_pool().get();
         b = event_pool().get();
         sweep_shape(cand[0], rows, R, lv.B, lv.dinv, X, nullptr, scratch);     // warm-up
         float bestms = 1e30f;
-        for (auto& c : cand) {
-            HIPCHK(hipEventRecord(a, s));
-            sweep_shape(c, rows, R, lv.B, lv.dinv, X, nullptr, scratch);
-            HIPCHK(hipEventRecord(b, s));
-            HIPCHK(hipEventSynchronize(b));
-            float ms = 0;
-            HIPCHK(hipEventElapsedTime(&ms, a, b));
-            if (ms < bestms) { bestms = ms; sh = c; }
-        }
+        for (int rep = 0; rep < 2; ++rep)       // each candidate's best of two
+            for (auto& c : cand) {
+                HIPCHK(hipEventRecord(a, s));
+                sweep_shape(c, rows, R, lv.B, lv.dinv, X, nullptr, scratch);
+                HIPCHK(hipEventRecord(b, s));
+                HIPCHK(hipEventSynchronize(b));
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, a, b));
+                if (ms < bestms) { bestms = ms; sh = c; }
+            }
         event_pool().put(a);
         event_pool().put(b);
         std::lock_guard<std::mutex> lk(tu.mu);
@@ -1055,7 +1073,7 @@ struct Engine : bamg_ctx {
         const long long tot = (long long)rows * G;
         if (tot >= (1LL << 31)) fail(BAMG_EINVAL, "level %d too large for one sweep launch", l);
         auto kern = vw == 4 ? k_mcgs_tv<T, T, 4> : vw == 2 ? k_mcgs_tv<T, T, 2> : k_mcgs_tv<T, T, 1>;
-        if (l == 0) { st.sweep_vw = vw; st.sweep_bs = BAMG_BLK; }
+        if (l == 0) { st.sweep_vw = vw; st.sweep_bs = BAMG_BLK; st.sweep_rp = 1; }
         for (int k = 0; k < nu; ++k) {
             std::pair<hipEvent_t, hipEvent_t> ev;
             if (profile) ev = ev_begin();
@@ -1074,7 +1092,7 @@ struct Engine : bamg_ctx {
         T* a = X;
         T* b = sweep_tmp;
         const SweepShape sh = pick_sweep_shape(l, R, X, sweep_tmp);
-        if (l == 0) { st.sweep_vw = sh.vw; st.sweep_bs = sh.bs; }
+        if (l == 0) { st.sweep_vw = sh.vw; st.sweep_bs = sh.bs; st.sweep_rp = sh.rp; }
         long long tot = (long long)rows * R;
         for (int k = 0; k < nu; ++k) {
             std::pair<hipEvent_t, hipEvent_t> ev;

@@ -490,18 +490,33 @@ __global__ void k_normalize_into(int n, const double* __restrict__ u, const doub
 
 __device__ __forceinline__ void lds_sync() { __syncthreads(); }
 
+// sqrt(s) for a normal s > 0 from v_rsq_f64, refined by one coupled
+// Goldschmidt step for (sqrt(s), 1/(2 sqrt(s))) and one Newton correction of
+// the root (within an ulp or so; far fewer dependent steps than the
+// correctly rounded library square root).
+__device__ __forceinline__ double sqrt_rsq(double s) {
+    const double r = __builtin_amdgcn_rsq(s);
+    double g = s * r, h = 0.5 * r;
+    const double e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    return fma(fma(-g, g, s), h, g);
+}
+
 // Householder vector of a 3-vector (x, y, z) (z = 0 for a 2-vector): with
 // a = -sign(x) ||(x, y, z)||, u = (x - a, y, z) and beta = 2 / u^T u, the
 // reflector I - beta u u^T maps (x, y, z) to (a, 0, 0).  beta = 0 when the
-// vector is already zero below its first entry.
+// vector is already zero below its first entry.  beta comes from u as
+// formed, so the reflector is orthogonal to rounding whatever the error of
+// the norm.
 __device__ __forceinline__ void house3(double x, double y, double z, double& u0, double& u1, double& u2,
                                        double& beta) {
     const double tail = y * y + z * z;
     if (tail == 0.0) { u0 = 1.0; u1 = 0.0; u2 = 0.0; beta = 0.0; return; }
-    const double nrm = sqrt(x * x + tail);
+    const double nrm = sqrt_rsq(x * x + tail);
     const double a = x >= 0.0 ? -nrm : nrm;
     u0 = x - a; u1 = y; u2 = z;
-    beta = 2.0 / (u0 * u0 + tail);
+    beta = 2.0 * cz_recip(u0 * u0 + tail);
 }
 
 // Eigenvalues of the m x m upper Hessenberg A (LDS, row-major, ld HQR_LD;
@@ -576,33 +591,39 @@ __device__ void francis_eigvals_wave(int m, double* A, double* wr, double* wi, i
         double y = h10 * (h00 + h11 - s);
         double z = h10 * HA(lo + 2, lo + 1);
         lds_sync();
+        // every lane reads a valid row and column of the window (its own,
+        // clamped); lanes outside the ranges below compute but do not store
+        const int jc = min(max(lane, lo), hi);
         for (int k = lo; k <= hi - 1; ++k) {
             const bool two = k == hi - 1;        // the last reflector spans 2 rows
+            const int k2 = two ? k + 1 : k + 2;  // its third row / column (read, unused, when two)
+            // rows k .. k+2 of column jc, read before the reflector is formed
+            const double a0 = HA(k, jc), a1 = HA(k + 1, jc), a2r = HA(k2, jc);
             double u0, u1, u2, beta;
             house3(x, y, two ? 0.0 : z, u0, u1, u2, beta);
             // rows k .. k+2 from the left, columns max(lo, k-1) .. hi
             {
-                const int j = lane;
-                if (j >= max(lo, k - 1) && j <= hi) {
-                    const double a0 = HA(k, j), a1 = HA(k + 1, j), a2 = two ? 0.0 : HA(k + 2, j);
-                    const double w = beta * (u0 * a0 + u1 * a1 + u2 * a2);
-                    HA(k, j) = a0 - w * u0;
-                    HA(k + 1, j) = a1 - w * u1;
-                    if (!two) HA(k + 2, j) = a2 - w * u2;
+                const double a2 = two ? 0.0 : a2r;
+                const double w = beta * (u0 * a0 + u1 * a1 + u2 * a2);
+                if (lane >= max(lo, k - 1) && lane <= hi) {
+                    HA(k, lane) = a0 - w * u0;
+                    HA(k + 1, lane) = a1 - w * u1;
+                    if (!two) HA(k + 2, lane) = a2 - w * u2;
                 }
             }
             lds_sync();
             // columns k .. k+2 from the right, rows lo .. min(k+3, hi)
-            double c0 = 0.0;
+            double c0;
             {
-                const int i = lane;
-                if (i >= lo && i <= min(k + 3, hi)) {
-                    const double a0 = HA(i, k), a1 = HA(i, k + 1), a2 = two ? 0.0 : HA(i, k + 2);
-                    const double w = beta * (a0 * u0 + a1 * u1 + a2 * u2);
-                    c0 = a0 - w * u0;
-                    HA(i, k) = c0;
-                    HA(i, k + 1) = a1 - w * u1;
-                    if (!two) HA(i, k + 2) = a2 - w * u2;
+                const int i = min(jc, min(k + 3, hi));
+                const double b0 = HA(i, k), b1 = HA(i, k + 1), b2r = HA(i, k2);
+                const double b2 = two ? 0.0 : b2r;
+                const double w = beta * (b0 * u0 + b1 * u1 + b2 * u2);
+                c0 = b0 - w * u0;
+                if (lane >= lo && lane <= min(k + 3, hi)) {
+                    HA(lane, k) = c0;
+                    HA(lane, k + 1) = b1 - w * u1;
+                    if (!two) HA(lane, k + 2) = b2 - w * u2;
                 }
             }
             // next reflector: column k below the diagonal, rows k+1 .. k+3

@@ -195,39 +195,60 @@ __device__ __forceinline__ void ld_nt_w4(const M* p, M* w) {
     }
 }
 
-template <typename T, typename M, int VW, int BS>
+// A thread takes RP row pieces spaced ceil(n G / RP) pieces apart: with two,
+// each wavefront has twice the loads in flight at the same occupancy.  The
+// index loads of all its pieces are issued first, then all gathers.
+template <typename T, typename M, int VW, int BS, int RP = 1>
 __global__ void __launch_bounds__(BS)
 k_sweep_ve(int n, int G, FastDiv divG, const int* __restrict__ eci, const M* __restrict__ ev,
            const M* __restrict__ dinv, const T* __restrict__ X, const T* __restrict__ F, T* __restrict__ Y) {
-    const int t = xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
-    if (t >= n * G) return;
-    const int i = (int)divG.div((uint32_t)t), kg = t - i * G;
+    const int tot = n * G, span = RP == 1 ? tot : (tot + RP - 1) / RP;
+    const int t0 = xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
+    if (t0 >= span) return;
     const int R = G * VW;
-    const size_t base = (size_t)i * R + (size_t)kg * VW;
-    const int4 c4 = ld_nt_i4(eci + (size_t)i * 4);
-    M w[4];
-    ld_nt_w4<M>(ev + (size_t)i * 4, w);
-    T xt[VW], f[VW], acc[VW];
-    VecIO<T, VW>::ld(X + base, xt);
-    if (F) VecIO<T, VW>::ld(F + base, f);
-    else
+    int i[RP], kg[RP];
+    bool ok[RP];
+    int4 c4[RP];
+    M w[RP][4];
+    T xt[RP][VW], f[RP][VW], d[RP];
 #pragma unroll
-        for (int q = 0; q < VW; ++q) f[q] = (T)0;
+    for (int h = 0; h < RP; ++h) {
+        const int t = t0 + h * span;
+        ok[h] = h == 0 || t < tot;
+        const int tt = ok[h] ? t : t0;            // a piece past the end redoes the first one
+        i[h] = (int)divG.div((uint32_t)tt);
+        kg[h] = tt - i[h] * G;
+        c4[h] = ld_nt_i4(eci + (size_t)i[h] * 4);
+        ld_nt_w4<M>(ev + (size_t)i[h] * 4, w[h]);
+        const size_t base = (size_t)i[h] * R + (size_t)kg[h] * VW;
+        VecIO<T, VW>::ld(X + base, xt[h]);
+        if (F) VecIO<T, VW>::ld(F + base, f[h]);
+        else
 #pragma unroll
-    for (int q = 0; q < VW; ++q) acc[q] = (T)0;
-    const T d = (T)__builtin_nontemporal_load(dinv + i);
-    const int c[4] = {c4.x, c4.y, c4.z, c4.w};
-    T x[4][VW];
+            for (int q = 0; q < VW; ++q) f[h][q] = (T)0;
+        d[h] = (T)__builtin_nontemporal_load(dinv + i[h]);
+    }
+    T x[RP][4][VW];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) VecIO<T, VW>::ld(X + (size_t)c[u] * R + (size_t)kg * VW, x[u]);
+    for (int h = 0; h < RP; ++h) {
+        const int c[4] = {c4[h].x, c4[h].y, c4[h].z, c4[h].w};
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 4; ++u) VecIO<T, VW>::ld(X + (size_t)c[u] * R + (size_t)kg[h] * VW, x[h][u]);
+    }
 #pragma unroll
-        for (int q = 0; q < VW; ++q) acc[q] += (T)w[u] * x[u][q];
-    T y[VW];
+    for (int h = 0; h < RP; ++h) {
+        T acc[VW];
 #pragma unroll
-    for (int q = 0; q < VW; ++q) y[q] = xt[q] + d * (f[q] - acc[q]);
-    StreamIO<T, VW>::st(Y + base, y);
+        for (int q = 0; q < VW; ++q) acc[q] = (T)0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < VW; ++q) acc[q] += (T)w[h][u] * x[h][u][q];
+        T y[VW];
+#pragma unroll
+        for (int q = 0; q < VW; ++q) y[q] = xt[h][q] + d[h] * (f[h][q] - acc[q]);
+        if (ok[h]) StreamIO<T, VW>::st(Y + (size_t)i[h] * R + (size_t)kg[h] * VW, y);
+    }
 }
 
 // ELL-4 copy of a CSR matrix (see k_sweep_ve); err = 1 when a row has more

@@ -227,9 +227,11 @@ def test_trim_returns_cached_memory_and_handles_still_work():
     assert torch.equal(x, x3)
 
 
-@pytest.mark.parametrize("variant", ["1,128", "2,256", "3,128", "4,512", "6,256", "12,128"])
+@pytest.mark.parametrize("variant", ["1,128", "2,256", "3,128", "4,512", "6,256", "12,128", "2,256,2", "4,512,2"])
 def test_sweep_variants_give_the_same_bits(variant, monkeypatch):
-    # every launch shape the autotuner may pick computes the same numbers
+    # every launch shape the autotuner may pick computes the same numbers;
+    # with two row pieces per thread the 1681 x 3 pieces leave the last
+    # thread's second piece past the end
     ch = C.tandem_queue(40)
     opts = B.default_options(levels=3, stop_after=1)
     monkeypatch.setenv("BAMG_SWEEP_VARIANT", "1,256")
@@ -237,5 +239,7 @@ def test_sweep_variants_give_the_same_bits(variant, monkeypatch):
     monkeypatch.setenv("BAMG_SWEEP_VARIANT", variant)
     h = B.Hierarchy.from_chain(ch, 12, opts)
     assert np.array_equal(h.export(0, B.X_U), ref)
-    vw, bs = map(int, variant.split(","))
-    assert (h.stats().sweep_vw, h.stats().sweep_bs) == (vw, bs)
+    vw, bs, *rp = map(int, variant.split(","))
+    st = h.stats()
+    assert st.sweep_ell == 1
+    assert (st.sweep_vw, st.sweep_bs, st.sweep_rp) == (vw, bs, rp[0] if rp else 1)
