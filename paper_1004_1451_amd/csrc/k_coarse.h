@@ -674,6 +674,47 @@ __device__ __forceinline__ void dc_stage2(double (*D1)[GJ_NB + 1], F1 f1, double
     }
 }
 
+// acc (dc_mfma layout) += A B for 64 x 64 operands A (entry (r, k) from
+// fa(r, k)) and B (entry (k, c) from fb(k, c)), k ascending as in dc_mfma.
+// The operands pass through LDS in chunks of DC_KC values of k (17 KB for
+// both), each chunk's loads issued while the previous chunk's products run,
+// so that several workgroups share a CU.
+#define DC_KC 16
+template <typename FA, typename FB>
+__device__ __forceinline__ void dc_rank64(FA fa, FB fb, double (*As)[DC_KC + 1], double (*Bs)[GJ_NB + 1], int wv,
+                                          int lane, dc_d4 (&acc)[4]) {
+    constexpr int NQ = GJ_NB * DC_KC / BAMG_BLK;
+    double ra[NQ], rb[NQ];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = threadIdx.x + q * BAMG_BLK;
+            ra[q] = fa(e / DC_KC, k0 + e % DC_KC);
+            rb[q] = fb(k0 + e / GJ_NB, e % GJ_NB);
+        }
+    };
+    load(0);
+    const int ar = 16 * wv + lane % 16, kq = lane / 16, bc = lane % 16;
+    for (int k0 = 0; k0 < GJ_NB; k0 += DC_KC) {
+        __syncthreads();                        // the previous chunk's products are done
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = threadIdx.x + q * BAMG_BLK;
+            As[e / DC_KC][e % DC_KC] = ra[q];
+            Bs[e / GJ_NB][e % GJ_NB] = rb[q];
+        }
+        __syncthreads();
+        if (k0 + DC_KC < GJ_NB) load(k0 + DC_KC);
+#pragma unroll
+        for (int kk = 0; kk < DC_KC / 4; ++kk) {
+            const double av = As[ar][4 * kk + kq];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+                acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Bs[4 * kk + kq][16 * cb + bc], acc[cb], 0, 0, 0);
+        }
+    }
+}
+
 // Leaves: W[k, k] = D_k^-1 (grid (block rows, chains)).
 __global__ void __launch_bounds__(BAMG_BLK)
 k_dc_leaf(const CoarseDesc* __restrict__ cd, double* __restrict__ Fp, double* __restrict__ Wp,
@@ -940,8 +981,8 @@ k_dc_panels(const CoarseDesc* __restrict__ cd, int t, double* __restrict__ Fp, c
 __global__ void __launch_bounds__(BAMG_BLK)
 k_dc_tiles(const CoarseDesc* __restrict__ cd, int t, const double* __restrict__ Pp, const double* __restrict__ Rp,
            int rld, double* __restrict__ Wp) {
-    __shared__ double As[GJ_NB][GJ_NB + 1];
-    __shared__ double Bs[GJ_NB][GJ_NB + 1];
+    __shared__ double As[GJ_NB][DC_KC + 1];
+    __shared__ double Bs[DC_KC][GJ_NB + 1];
     const CoarseDesc d = cd[blockIdx.y];
     if (!dc_plain(d)) return;
     const int S = min(2 << t, d.nx);
@@ -955,27 +996,24 @@ k_dc_tiles(const CoarseDesc* __restrict__ cd, int t, const double* __restrict__ 
     const int b = d.ny, n = d.n, tid = threadIdx.x, c = tid % BAMG_WAVE, w = tid / BAMG_WAVE;
     const double* P = Pp + (size_t)(d.voff + I * b) * (2 * GJ_NB) + side * GJ_NB;
     double* W = Wp + d.woff + (size_t)(I * b) * n + J * b;
-    // the tile's current entries first (same side), in flight with the panels
-    double old[4][4];
-#pragma unroll
-    for (int q2 = 0; q2 < 4; ++q2)
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-            const int row = dc_row(w, c, q2), col = dc_col(c, cb);
-            old[q2][cb] = (same && row < b && col < b) ? W[(size_t)row * n + col] : 0.0;
-        }
-    dc_stage2(As, [&](int r, int cc) { return r < b ? P[(size_t)r * 2 * GJ_NB + cc] : 0.0; },
-              Bs, [&](int r, int cc) { return (r < b && cc < b) ? Rp[(size_t)r * rld + d.voff + J * b + cc] : 0.0; });
-    __syncthreads();
+    // the accumulators start from the tile's current entries (same side)
     dc_d4 acc[4];
-    dc_zero(acc);
-    dc_mfma(As, Bs, w, c, acc);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int q2 = 0; q2 < 4; ++q2) {
+            const int row = dc_row(w, c, q2), col = dc_col(c, cb);
+            acc[cb][q2] = (same && row < b && col < b) ? W[(size_t)row * n + col] : 0.0;
+        }
+    dc_rank64([&](int r, int k) { return r < b ? P[(size_t)r * 2 * GJ_NB + k] : 0.0; },
+              [&](int k, int cc) { return (k < b && cc < b) ? Rp[(size_t)k * rld + d.voff + J * b + cc] : 0.0; },
+              As, Bs, w, c, acc);
 #pragma unroll
     for (int q2 = 0; q2 < 4; ++q2)
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
             const int row = dc_row(w, c, q2), col = dc_col(c, cb);
-            if (row < b && col < b) W[(size_t)row * n + col] = old[q2][cb] + acc[cb][q2];
+            if (row < b && col < b) W[(size_t)row * n + col] = acc[cb][q2];
         }
 }
 
@@ -1100,55 +1138,33 @@ k_bd_gh(const CoarseDesc* __restrict__ cd, const CoarseDesc* __restrict__ cs, co
 }
 
 // W (natural order) from the pieces: grid (nx, nx) workgroups for the main x
-// main tiles (grid rows a, a2): W = A^-1 + G Y, the rank-ne product summed
-// over e ascending in chunks of 16 staged through LDS; thread (ty, tx) takes
-// rows ty + 16 p and columns tx + 16 q.
-#define BD_KC 16
+// main tiles (grid rows a, a2): W = A^-1 + G Y, the rank-ne product (ne <= 64,
+// zero beyond) on the FP64 matrix cores with e ascending, added to the tile
+// of A^-1 held in the accumulators.
 __global__ void __launch_bounds__(BAMG_BLK)
 k_bd_combine_main(const CoarseDesc* __restrict__ cd, const CoarseDesc* __restrict__ cs, double* __restrict__ Wp,
                   const double* __restrict__ G, const double* __restrict__ Y) {
-    static_assert(BAMG_BLK == 256 && BD_B == 64, "16 x 16 threads on a 64 x 64 tile");
-    __shared__ double Gs[BD_B][BD_KC + 1];
-    __shared__ double Ys[BD_KC][BD_B + 1];
+    static_assert(BAMG_BLK == 256 && BD_B == GJ_NB, "four wavefronts on a 64 x 64 tile");
+    __shared__ double As[GJ_NB][DC_KC + 1];
+    __shared__ double Bs[DC_KC][GJ_NB + 1];
     const CoarseDesc d = cd[0], m = cs[0];
     const int ne = d.nx - 1, nm = m.n, n = d.n;
     const double* Am = Wp + m.woff;
     double* W = Wp + d.woff;
-    const int a = blockIdx.y, a2 = blockIdx.x;
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    const int i0 = a * BD_B, j0 = a2 * BD_B;
-    double acc[4][4];
+    const int i0 = blockIdx.y * BD_B, j0 = blockIdx.x * BD_B;
+    const int c = threadIdx.x % BAMG_WAVE, w = threadIdx.x / BAMG_WAVE;
+    dc_d4 acc[4];
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] = Am[(size_t)(i0 + ty + 16 * p) * nm + j0 + tx + 16 * q];
-    for (int e0 = 0; e0 < ne; e0 += BD_KC) {
-        __syncthreads();
-        for (int t = threadIdx.x; t < BD_B * BD_KC; t += BAMG_BLK) {
-            const int r = t / BD_KC, k = t % BD_KC;
-            Gs[r][k] = (e0 + k < ne) ? G[(size_t)(i0 + r) * BD_B + e0 + k] : 0.0;
-            const int k2 = t / BD_B, c = t % BD_B;
-            Ys[k2][c] = (e0 + k2 < ne) ? Y[(size_t)(e0 + k2) * nm + j0 + c] : 0.0;
-        }
-        __syncthreads();
+        for (int q = 0; q < 4; ++q) acc[cb][q] = Am[(size_t)(i0 + dc_row(w, c, q)) * nm + j0 + dc_col(c, cb)];
+    dc_rank64([&](int r, int k) { return k < ne ? G[(size_t)(i0 + r) * BD_B + k] : 0.0; },
+              [&](int k, int cc) { return k < ne ? Y[(size_t)k * nm + j0 + cc] : 0.0; }, As, Bs, w, c, acc);
+    const int r0 = blockIdx.y * (BD_B + 1), c0 = blockIdx.x * (BD_B + 1);
 #pragma unroll
-        for (int k = 0; k < BD_KC; ++k) {
-            double gv[4], yv[4];
+    for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-            for (int p = 0; p < 4; ++p) gv[p] = Gs[ty + 16 * p][k];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) yv[q] = Ys[k][tx + 16 * q];
-#pragma unroll
-            for (int p = 0; p < 4; ++p)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[p][q] = fma(gv[p], yv[q], acc[p][q]);
-        }
-    }
-    const int r0 = a * (BD_B + 1), c0 = a2 * (BD_B + 1);
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) W[(size_t)(r0 + ty + 16 * p) * n + c0 + tx + 16 * q] = acc[p][q];
+        for (int q = 0; q < 4; ++q) W[(size_t)(r0 + dc_row(w, c, q)) * n + c0 + dc_col(c, cb)] = acc[cb][q];
 }
 
 // The border rows and columns of W: row of border point e: -H (main
@@ -1484,8 +1500,20 @@ __global__ void k_cz_arn_dots2(const CoarseDesc* __restrict__ cd, int j, const d
     if (j >= d.am || b > j + 1) return;
     const double* u = Vb + d.aoff + (size_t)(j + 1) * d.n;
     const double* x = b == 0 ? cvec + d.voff : Vb + d.aoff + (size_t)(b - 1) * d.n;
+    // i ascending in steps of the block, 8 rows' loads issued together
     double s = 0;
-    for (int i = threadIdx.x; i < d.n; i += BAMG_BLK) s += x[i] * u[i];
+    for (int i0 = threadIdx.x; i0 < d.n; i0 += 8 * BAMG_BLK) {
+        double xv[8], uv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int i = i0 + q * BAMG_BLK;
+            xv[q] = i < d.n ? x[i] : 0.0;
+            uv[q] = i < d.n ? u[i] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (i0 + q * BAMG_BLK < d.n) s += xv[q] * uv[q];
+    }
     s = block_sum(s, sh);
     if (threadIdx.x == 0) dots[(size_t)blockIdx.y * DS + b] = s;
 }
@@ -1582,8 +1610,17 @@ k_cz_arn_updatep(const CoarseDesc* __restrict__ cd, int j, const double* __restr
     const int G = gridDim.x;
     for (int b = threadIdx.x; b < K; b += BAMG_BLK) {
         double s = 0;
-        if (b <= j)
-            for (int g = 0; g < G; ++g) s += apart[((size_t)blockIdx.y * DS + b) * G + g];
+        if (b <= j) {
+            const double* pb = apart + ((size_t)blockIdx.y * DS + b) * G;
+            for (int g0 = 0; g0 < G; g0 += 8) {     // in block order, 8 loads in flight
+                double v[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v[q] = g0 + q < G ? pb[g0 + q] : 0.0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (g0 + q < G) s += v[q];
+            }
+        }
         dt[b] = s;
     }
     __syncthreads();
@@ -1614,32 +1651,59 @@ __global__ void k_cz_arn_normtv(const CoarseDesc* __restrict__ cd, int j, const 
                                 int DS, const double* __restrict__ npart, double* __restrict__ w) {
     const CoarseDesc d = cd[blockIdx.y];
     if (j >= d.am) return;
+    const double* u = ub + d.voff;
+    double* v = Vb + d.aoff + (size_t)(j + 1) * d.n;
+    const M* tv = (const M*)d.tv;
+    // this thread's row of T first: its entries and the neighbours' u are
+    // loaded while the norm's partials are summed
+    constexpr int TR = 9;
+    const int i = blockIdx.x * BAMG_BLK + threadIdx.x;
+    int p0 = 0, p1 = 0;
+    if (d.trp && i < d.n) { p0 = d.trp[d.row0 + i]; p1 = d.trp[d.row0 + i + 1]; }
     const double* pp = npart + (size_t)blockIdx.y * gridDim.x * 2;
     double s = 0, t = 0;
-    for (int q = 0; q < (int)gridDim.x; ++q) { s += pp[2 * q]; t += pp[2 * q + 1]; }
+    for (int q0 = 0; q0 < (int)gridDim.x; q0 += 8) {   // in block order, 8 pairs in flight
+        double a[8], c[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const bool ok = q0 + q < (int)gridDim.x;
+            a[q] = ok ? pp[2 * (q0 + q)] : 0.0;
+            c[q] = ok ? pp[2 * (q0 + q) + 1] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q0 + q < (int)gridDim.x) { s += a[q]; t += c[q]; }
+    }
+    double tw[TR], uc[TR];
+#pragma unroll
+    for (int k = 0; k < TR; ++k) {
+        const int p = p0 + k;
+        const bool ok = p < p1;
+        tw[k] = ok ? (double)tv[p] : 0.0;
+        uc[k] = ok ? u[d.tci[p] - d.row0] : 0.0;
+    }
     const double nrm = sqrt(s);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         H[(size_t)blockIdx.y * HS + (size_t)j * (d.am + 1) + j + 1] = nrm;
         vy[(size_t)blockIdx.y * DS + j + 1] = nrm > 0 ? t / nrm : 0.0;
     }
-    const double* u = ub + d.voff;
-    double* v = Vb + d.aoff + (size_t)(j + 1) * d.n;
-    for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < d.n; i += gridDim.x * BAMG_BLK) {
-        const double vi = nrm > 0 ? u[i] / nrm : 0.0;
-        v[i] = vi;
+    for (int r = i; r < d.n; r += gridDim.x * BAMG_BLK) {
+        const double vi = nrm > 0 ? u[r] / nrm : 0.0;
+        v[r] = vi;
         double tvs;
         if (!d.trp) {
             tvs = vi;
         } else {
-            const M* tv = (const M*)d.tv;
+            // the neighbours' entries divided the same way as the basis column
             tvs = 0;
-            const int gi = d.row0 + i;
-            for (int p = d.trp[gi]; p < d.trp[gi + 1]; ++p) {
-                const int col = d.tci[p] - d.row0;
-                tvs += (double)tv[p] * (nrm > 0 ? u[col] / nrm : 0.0);
-            }
+            const int q0 = r == i ? p0 : d.trp[d.row0 + r], q1 = r == i ? p1 : d.trp[d.row0 + r + 1];
+#pragma unroll
+            for (int k = 0; k < TR; ++k)
+                if (r == i && p0 + k < p1) tvs += tw[k] * (nrm > 0 ? uc[k] / nrm : 0.0);
+            for (int p = r == i ? q0 + TR : q0; p < q1; ++p)
+                tvs += (double)tv[p] * (nrm > 0 ? u[d.tci[p] - d.row0] / nrm : 0.0);
         }
-        w[d.voff + i] = tvs;
+        w[d.voff + r] = tvs;
     }
 }
 
