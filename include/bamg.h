@@ -194,7 +194,12 @@ typedef struct {
                                    columns per thread, threads per workgroup
                                    (VW 1, 2, 3, 4, 6 or 12; autotuned once per shape and process;
                                    BAMG_SWEEP_VARIANT="VW,BS[,RP]" forces one) */
-    double tune_ms;         /* process total spent timing sweep candidates    */
+    double tune_ms;         /* process total spent timing launch candidates
+                               (level-0 and coarse sweeps; the fused Galerkin
+                               launch's 14, 28 or 56 coarse rows per
+                               workgroup, BAMG_GAL_ROWS forcing one); with
+                               BAMG_TUNE_CACHE=<file> the choices are read
+                               from and written to that JSON file          */
     int64_t mlp_points;     /* learned form: F points judged (all levels)      */
     int64_t mlp_fallback;   /* of which fell back to the least-squares row     */
     /* with options.profile: the rank-64 updates of the dense coarsest inverse

@@ -226,15 +226,99 @@ DeviceCache& device_cache() {
 // BAMG_SWEEP_VARIANT="VW,BS[,RP]" in the environment forces a variant.
 struct SweepShape { int vw = 1, bs = 256, rp = 1; };
 
+// The tuner also picks the coarse rows per workgroup of the fused Galerkin
+// launch (14, 28 or 56) per (device, coarse rows, operator forms, type).
+// With BAMG_TUNE_CACHE=<path> the choices persist across processes as one
+// JSON object, {"<arch>|<kernel>|<shape ...>": [choice ...], ...}: read at the
+// first tuner use, rewritten (through a temporary file) after each new choice.
 struct SweepTuner {
     std::mutex mu;
     std::map<std::tuple<int, int, int, int, int>, SweepShape> best;
+    std::map<std::tuple<int, int, int, int, int>, int> gal_rows;
+    std::map<std::string, std::vector<int>> file;     // entries of the cache file
+    bool file_read = false;
     double tune_ms = 0;
 };
 
 SweepTuner& sweep_tuner() {
     static SweepTuner* t = new SweepTuner();
     return *t;
+}
+
+const char* tune_cache_path() {
+    const char* e = getenv("BAMG_TUNE_CACHE");
+    return e && *e ? e : nullptr;
+}
+
+std::string device_arch(int dev) {
+    hipDeviceProp_t pr;
+    if (hipGetDeviceProperties(&pr, dev) != hipSuccess) return "unknown";
+    std::string a = pr.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// Entries of the cache file into tu.file (once per process; caller holds tu.mu).
+void tune_cache_read(SweepTuner& tu) {
+    if (tu.file_read) return;
+    tu.file_read = true;
+    const char* path = tune_cache_path();
+    if (!path) return;
+    FILE* f = fopen(path, "rb");
+    if (!f) return;
+    std::string txt;
+    char buf[4096];
+    size_t k;
+    while ((k = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, k);
+    fclose(f);
+    size_t pos = 0;
+    while (true) {
+        const size_t q0 = txt.find('"', pos);
+        if (q0 == std::string::npos) break;
+        const size_t q1 = txt.find('"', q0 + 1);
+        const size_t b0 = q1 == std::string::npos ? q1 : txt.find('[', q1);
+        const size_t b1 = b0 == std::string::npos ? b0 : txt.find(']', b0);
+        if (b1 == std::string::npos) break;
+        std::vector<int> v;
+        const char* p = txt.c_str() + b0 + 1;
+        const char* end = txt.c_str() + b1;
+        while (p < end) {
+            char* nx = nullptr;
+            const long x = strtol(p, &nx, 10);
+            if (nx == p) { ++p; continue; }
+            v.push_back((int)x);
+            p = nx;
+        }
+        tu.file[txt.substr(q0 + 1, q1 - q0 - 1)] = v;
+        pos = b1 + 1;
+    }
+}
+
+// Rewrite the cache file with tu.file (caller holds tu.mu); failures to
+// write only lose the cache.
+void tune_cache_write(const SweepTuner& tu) {
+    const char* path = tune_cache_path();
+    if (!path) return;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "wb");
+    if (!f) return;
+    fputs("{", f);
+    bool first = true;
+    for (const auto& kv : tu.file) {
+        fprintf(f, "%s\n  \"%s\": [", first ? "" : ",", kv.first.c_str());
+        for (size_t i = 0; i < kv.second.size(); ++i) fprintf(f, "%s%d", i ? ", " : "", kv.second[i]);
+        fputs("]", f);
+        first = false;
+    }
+    fputs("\n}\n", f);
+    const bool ok = fclose(f) == 0;
+    if (ok) (void)rename(tmp.c_str(), path);
+}
+
+std::string tune_key(int dev, const char* kernel, std::initializer_list<long long> shape) {
+    std::string k = device_arch(dev) + "|" + kernel;
+    for (long long x : shape) k += "|" + std::to_string(x);
+    return k;
 }
 
 bool forced_sweep_shape(int R, SweepShape& out) {
@@ -1009,10 +1093,21 @@ struct Engine : bamg_ctx {
         const int nnz = l == 0 ? nnz0 : -1;
         auto key = std::make_tuple(dev, rows, R, nnz, (int)sizeof(T));
         auto& tu = sweep_tuner();
+        const std::string fkey = tune_key(dev, "sweep", {rows, R, nnz, (long long)sizeof(T), lv.B.eci ? 1 : 0});
         {
             std::lock_guard<std::mutex> lk(tu.mu);
             auto it = tu.best.find(key);
             if (it != tu.best.end()) return it->second;
+            tune_cache_read(tu);
+            auto ft = tu.file.find(fkey);
+            if (ft != tu.file.end() && ft->second.size() == 3) {
+                SweepShape c{ft->second[0], ft->second[1], ft->second[2]};
+                const bool known = (c.vw == 1 || c.vw == 2 || c.vw == 3 || c.vw == 4 || c.vw == 6 || c.vw == 12) &&
+                                   R % c.vw == 0 && (c.bs == 128 || c.bs == 256 || c.bs == 512) &&
+                                   (c.vw <= 2 || c.vw == 4 || c.bs <= 256) &&
+                                   (c.rp == 1 || (c.rp == 2 && lv.B.eci && (c.vw == 2 || c.vw == 4) && c.bs >= 256));
+                if (known) { tu.best[key] = c; return c; }
+            }
         }
         auto t0 = std::chrono::steady_clock::now();
         std::vector<SweepShape> cand;
@@ -1042,6 +1137,8 @@ struct Engine : bamg_ctx {
         event_pool().put(b);
         std::lock_guard<std::mutex> lk(tu.mu);
         tu.best[key] = sh;
+        tu.file[fkey] = {sh.vw, sh.bs, sh.rp};
+        tune_cache_write(tu);
         tu.tune_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         return sh;
     }
@@ -1143,33 +1240,105 @@ struct Engine : bamg_ctx {
         return !(e && e[0] == '0');
     }
 
+    // Coarse rows per workgroup of the fused Galerkin launch: forced, cached,
+    // or tuned now by timing each candidate twice in place (each writes the
+    // same outputs).  Below 2^16 coarse rows, and with a CSR operand, 28.
+    template <typename RUN>
+    int pick_gal_rows(int nc, int efb, int eft, RUN&& run) {
+        if (const int g = forced_gal_rows()) return g;
+        if (nc < (1 << 16) || efb == EF_CSR || eft == EF_CSR) return GAL_ROWS;
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        auto key = std::make_tuple(dev, nc, efb, eft, (int)sizeof(T));
+        const std::string fkey = tune_key(dev, "galerkin", {nc, efb, eft, (long long)sizeof(T)});
+        auto& tu = sweep_tuner();
+        {
+            std::lock_guard<std::mutex> lk(tu.mu);
+            auto it = tu.gal_rows.find(key);
+            if (it != tu.gal_rows.end()) return it->second;
+            tune_cache_read(tu);
+            auto ft = tu.file.find(fkey);
+            if (ft != tu.file.end() && ft->second.size() == 1 &&
+                (ft->second[0] == 14 || ft->second[0] == 28 || ft->second[0] == 56)) {
+                tu.gal_rows[key] = ft->second[0];
+                return ft->second[0];
+            }
+        }
+        auto t0 = std::chrono::steady_clock::now();
+        hipEvent_t a = event_pool().get(), b = event_pool().get();
+        float bestms = 1e30f;
+        int best = GAL_ROWS;
+        for (int rep = 0; rep < 2; ++rep)
+            for (int gr : {14, 28, 56}) {
+                HIPCHK(hipEventRecord(a, s));
+                run(gr);
+                HIPCHK(hipEventRecord(b, s));
+                HIPCHK(hipEventSynchronize(b));
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, a, b));
+                if (ms < bestms) { bestms = ms; best = gr; }
+            }
+        event_pool().put(a);
+        event_pool().put(b);
+        std::lock_guard<std::mutex> lk(tu.mu);
+        tu.gal_rows[key] = best;
+        tu.file[fkey] = {best};
+        tune_cache_write(tu);
+        tu.tune_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return best;
+    }
+
     // Both Galerkin products of a grid level in one launch (ELL-9 output),
     // then their CSR forms and the next level's D^-1.
+    // BAMG_GAL_ROWS=14|28|56 in the environment forces the fused Galerkin
+    // launch's coarse rows per workgroup.
+    static int forced_gal_rows() {
+        const char* e = getenv("BAMG_GAL_ROWS");
+        const int g = e ? atoi(e) : 0;
+        return g == 14 || g == 28 || g == 56 ? g : 0;
+    }
+
     void galerkin(int l, bool profile) {
         auto& f = L[l];
         auto& c = L[l + 1];
         const int nc = c.rows;
-        const int gb = ceil_div(nc, GAL_ROWS);
         // B_l's rows from its ELL copy; T_l's from its ELL-9 copy (T_0 = I)
         const EllSrc eb = ell_of(l);
         const EllSrc et = l == 0 ? EllSrc{nullptr, nullptr, 0, -1}
                         : f.Tm.cci ? EllSrc{f.Tm.cci, f.Tm.cv, f.Tm.cld, EF_ELL9}
                                    : EllSrc{nullptr, nullptr, 0, EF_CSR};
+        // one launch with gr coarse rows per workgroup (every choice gives
+        // the same bits); the ELL forms take the tuned choice
+        auto run = [&](int gr) {
+            ef_dispatch(eb.ef, [&](auto efb) {
+                constexpr int EFB = decltype(efb)::value;
+                auto launch = [&](auto eft) {
+                    constexpr int EFT = decltype(eft)::value;
+                    auto go = [&](auto grc) {
+                        constexpr int GR = decltype(grc)::value;
+                        LAUNCH((k_galerkin_bt<T, EFB, EFT, GR>), ceil_div(nc, GR), 9 * GR, s, nc,
+                               (const ChainGeo*)c.dgeo, c.nch, f.qc, (const T*)f.qv, (const int*)f.B.rp,
+                               (const int*)f.B.ci, (const T*)f.B.v, eb.c, eb.v, eb.ld, (const int*)f.Tm.rp,
+                               (const int*)f.Tm.ci, (const T*)f.Tm.v, et.c, et.v, et.ld, f.pc, (const T*)f.pv, c.B.gci,
+                               c.B.gv, f.cnt, c.Tm.gci, c.Tm.gv, f.cnt2);
+                    };
+                    if constexpr (EFB != EF_CSR && EFT != EF_CSR) {
+                        if (gr == 14) go(std::integral_constant<int, 14>{});
+                        else if (gr == 56) go(std::integral_constant<int, 56>{});
+                        else go(std::integral_constant<int, GAL_ROWS>{});
+                    } else {
+                        go(std::integral_constant<int, GAL_ROWS>{});
+                    }
+                };
+                if (et.ef < 0) launch(std::integral_constant<int, -1>{});
+                else if (et.ef == EF_ELL9) launch(std::integral_constant<int, EF_ELL9>{});
+                else launch(std::integral_constant<int, EF_CSR>{});
+            });
+        };
+        const int gr = pick_gal_rows(nc, eb.ef, et.ef, run);
         std::pair<hipEvent_t, hipEvent_t> ev;
         if (profile) ev = ev_begin();
-        ef_dispatch(eb.ef, [&](auto efb) {
-            constexpr int EFB = decltype(efb)::value;
-            auto launch = [&](auto eft) {
-                constexpr int EFT = decltype(eft)::value;
-                LAUNCH((k_galerkin_bt<T, EFB, EFT>), gb, GAL_THREADS, s, nc, (const ChainGeo*)c.dgeo, c.nch, f.qc,
-                       (const T*)f.qv, (const int*)f.B.rp, (const int*)f.B.ci, (const T*)f.B.v, eb.c, eb.v, eb.ld,
-                       (const int*)f.Tm.rp, (const int*)f.Tm.ci, (const T*)f.Tm.v, et.c, et.v, et.ld, f.pc,
-                       (const T*)f.pv, c.B.gci, c.B.gv, f.cnt, c.Tm.gci, c.Tm.gv, f.cnt2);
-            };
-            if (et.ef < 0) launch(std::integral_constant<int, -1>{});
-            else if (et.ef == EF_ELL9) launch(std::integral_constant<int, EF_ELL9>{});
-            else launch(std::integral_constant<int, EF_CSR>{});
-        });
+        run(gr);
         if (profile) ev_end(ev, ev_gal);
         scan(nc, f.cnt, c.B.rp);
         scan(nc, f.cnt2, c.Tm.rp);

@@ -1416,8 +1416,8 @@ __device__ __forceinline__ unsigned gal_slot(int coff, int Ia, int Ib, int i, co
     return mask;
 }
 
-// The output stage of the Galerkin kernels (all GAL_THREADS threads of the
-// block call it): thread (lr, s) of coarse row I (valid when I < nc) brings its
+// The output stage of the Galerkin kernels (all threads of the block call
+// it): thread (lr, s) of coarse row I (valid when I < nc) brings its
 // slot sums tb / tt and box masks mb / mt; the nine threads of a row add the
 // sums per box slot in order s = 0..8 through LDS (sv, sm) and thread u writes
 // box slot u at its rank among the row's structural slots into the
@@ -1469,8 +1469,9 @@ __device__ __forceinline__ void gal_write(int I, int nc, int lr, int s, int Ia, 
 }
 
 // Both products of a grid level in one pass: B_{l+1} = Q (B_l P) and
-// T_{l+1} = Q (T_l P) (Algorithm 3), nine threads per coarse row I (GAL_ROWS
-// rows per block), thread (I, s) taking slot s of Q row I (fine point
+// T_{l+1} = Q (T_l P) (Algorithm 3), nine threads per coarse row I (GR rows
+// per block, a launch shape the autotuner picks), thread (I, s) taking slot s
+// of Q row I (fine point
 // i = qc[9I + s]) for both products, so Q and P are read once.  B_l's rows
 // come from the storage EFB names, T_l's from EFT (EFT < 0: T_l = I).  The
 // sums are those of the separate numeric pass: q_Is (sum_j m_ij p_jJ) in
@@ -1480,8 +1481,8 @@ __device__ __forceinline__ void gal_write(int I, int nc, int lr, int s, int Ia, 
 // I at its rank among the row's structural slots (ascending column) into the
 // column-major ELL-9 arrays of each product (slot k of row I at k nc + I),
 // the free slots padded with (I, 0); *cnt[I] = structural slots of the row.
-template <typename MV, int EFB, int EFT>
-__global__ void __launch_bounds__(GAL_THREADS)
+template <typename MV, int EFB, int EFT, int GR = GAL_ROWS>
+__global__ void __launch_bounds__(9 * GR)
 k_galerkin_bt(int nc, const ChainGeo* __restrict__ geoc, int nch, const int* __restrict__ qc,
               const MV* __restrict__ qv, const int* __restrict__ brp, const int* __restrict__ bci,
               const MV* __restrict__ bv, const int* __restrict__ beci, const MV* __restrict__ bev, int beld,
@@ -1489,10 +1490,10 @@ k_galerkin_bt(int nc, const ChainGeo* __restrict__ geoc, int nch, const int* __r
               const int* __restrict__ teci, const MV* __restrict__ tev, int teld, const int* __restrict__ pc,
               const MV* __restrict__ pv, int* __restrict__ bcc, MV* __restrict__ bcv, int* __restrict__ bcnt,
               int* __restrict__ tcc, MV* __restrict__ tcv, int* __restrict__ tcnt) {
-    __shared__ MV sv[GAL_THREADS][9];
-    __shared__ unsigned sm[GAL_THREADS];
+    __shared__ MV sv[9 * GR][9];
+    __shared__ unsigned sm[9 * GR];
     const int lr = threadIdx.x / 9, s = threadIdx.x % 9;
-    const int I = xcd_tile(blockIdx.x, gridDim.x) * GAL_ROWS + lr;
+    const int I = xcd_tile(blockIdx.x, gridDim.x) * GR + lr;
     MV tb[9], tt[9];
 #pragma unroll
     for (int u = 0; u < 9; ++u) { tb[u] = 0; tt[u] = 0; }

@@ -243,3 +243,55 @@ def test_sweep_variants_give_the_same_bits(variant, monkeypatch):
     st = h.stats()
     assert st.sweep_ell == 1
     assert (st.sweep_vw, st.sweep_bs, st.sweep_rp) == (vw, bs, rp[0] if rp else 1)
+
+
+@pytest.mark.parametrize("rows", ["14", "56"])
+def test_galerkin_rows_per_workgroup_give_the_same_bits(rows, monkeypatch):
+    # the fused Galerkin launch shapes the autotuner chooses from (14, 28 or
+    # 56 coarse rows per workgroup) compute the same operators, level 0
+    # (T_0 = I, ELL-4 B_0) and the coarser levels (ELL-9 B_l and T_l)
+    ch = C.tandem_queue(40)
+    opts = B.default_options(levels=4, stop_after=1)
+    items = (B.X_B_COL, B.X_B_VAL, B.X_T_COL, B.X_T_VAL)
+    monkeypatch.setenv("BAMG_GAL_ROWS", "28")
+    h = B.Hierarchy.from_chain(ch, 12, opts)
+    ref = [[h.export(l, it) for it in items] for l in (1, 2, 3)]
+    h.close()
+    monkeypatch.setenv("BAMG_GAL_ROWS", rows)
+    h = B.Hierarchy.from_chain(ch, 12, opts)
+    for l, want in zip((1, 2, 3), ref):
+        for it, w in zip(items, want):
+            assert np.array_equal(h.export(l, it), w), (l, it)
+    h.close()
+
+
+def test_tune_cache_file_is_written_and_reused(tmp_path):
+    # a chain large enough that both tuners run (level-0 sweep: n R >= 2^20;
+    # Galerkin: level 1 with >= 2^16 coarse rows); a second process reads the
+    # choices from the cache file and times nothing
+    import json
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.json"
+    code = (
+        "import sys, json; sys.path.insert(0, %r)\n"
+        "import torch\n"
+        "from paper_1004_1451_amd import bamg as B, chains as C\n"
+        "ch = C.tandem_queue(512)\n"
+        "h = B.Hierarchy.from_chain(ch, 12, B.default_options(levels=4, stop_after=1))\n"
+        "st = h.stats()\n"
+        "print(json.dumps({'tune_ms': st.tune_ms, 'vw': st.sweep_vw, 'bs': st.sweep_bs, 'rp': st.sweep_rp}))\n"
+    ) % str(__import__("pathlib").Path(__file__).resolve().parents[1])
+    env = dict(__import__("os").environ, BAMG_TUNE_CACHE=str(cache))
+    env.pop("BAMG_SWEEP_VARIANT", None)
+    env.pop("BAMG_GAL_ROWS", None)
+    runs = []
+    for _ in range(2):
+        out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+        assert out.returncode == 0, out.stderr[-2000:]
+        runs.append(json.loads(out.stdout.strip().splitlines()[-1]))
+    entries = json.loads(cache.read_text())
+    kinds = {k.split("|")[1] for k in entries}
+    assert {"sweep", "galerkin"} <= kinds, entries
+    assert runs[0]["tune_ms"] > 0 and runs[1]["tune_ms"] == 0
+    assert (runs[0]["vw"], runs[0]["bs"], runs[0]["rp"]) == (runs[1]["vw"], runs[1]["bs"], runs[1]["rp"])
