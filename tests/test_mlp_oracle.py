@@ -141,3 +141,36 @@ def test_one_slot_feature_is_the_least_squares_weight():
         p[t] = b[i][t] / G[i][t, t]
         assert Lfit <= M.ls_functional(G[i], b[i], sigma[i], p) + 1e-12 * sigma[i]
     assert Lfit >= -1e-12 * sigma[i]
+
+
+def test_stencil_features_by_geometric_offset():
+    # one stored off-diagonal entry per row, at a known offset (da, db) in the
+    # 3 x 3 box; its -b_ij / b_ii must land in the feature the offset names:
+    # features 4..11 are the offsets in row-major order without the centre
+    import scipy.sparse as sp
+    order = [(-1, -1), (-1, 0), (-1, 1), (0, -1), (0, 1), (1, -1), (1, 0), (1, 1)]
+    for periodic in (False, True):
+        g = O.Grid(7, 6, periodic)
+        n = g.n
+        isC = O.is_c_point(g)
+        X = np.random.default_rng(5).random((n, 3)) + 0.5
+        w = np.ones(3)
+        for f_idx, (da, db) in enumerate(order):
+            rows, cols, vals = [], [], []
+            for p in range(n):
+                a, b = divmod(p, g.ny)
+                a2, b2 = a + da, b + db
+                if periodic:
+                    a2, b2 = a2 % g.nx, b2 % g.ny
+                rows.append(p); cols.append(p); vals.append(2.0 + p % 3)
+                if 0 <= a2 < g.nx and 0 <= b2 < g.ny:
+                    rows.append(p); cols.append(a2 * g.ny + b2); vals.append(-0.25 - 0.01 * (p % 7))
+            Bm = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+            F, *_ = M.level_features(X, w, Bm, g)
+            for p in np.nonzero(~isC)[0]:
+                a, b = divmod(p, g.ny)
+                inside = periodic or (0 <= a + da < g.nx and 0 <= b + db < g.ny)
+                want = np.zeros(8)
+                if inside:
+                    want[f_idx] = (0.25 + 0.01 * (p % 7)) / (2.0 + p % 3)
+                assert np.allclose(F[p, 4:12], want, rtol=1e-15, atol=0), (periodic, (da, db), p)

@@ -527,3 +527,20 @@ def test_cycle_counts_stay_flat_on_even_sides(N):
         assert info.converged
         counts.append(info.cycles)
     assert counts[0] <= counts[1] + 2 and counts[0] <= 10, counts
+
+
+def test_tv_weights_floor_for_null_vectors():
+    # omega_k = 1 / max(||B x_k||^2, (1e-14 ||x_k||)^2): a vector B maps to
+    # zero exactly (a symmetric two-state chain and the constant vector) gets
+    # the floor's finite weight, a scaled copy the same weight over c^2, and
+    # an ordinary vector the plain inverse squared residual
+    import scipy.sparse as sp
+    A = sp.csr_matrix(np.array([[0.5, 0.5], [0.5, 0.5]]))
+    B = O.b_from_a(A)
+    X = np.array([[1.0, 3.0, 1.0], [1.0, 3.0, 0.0]])
+    w = O.tv_weights(B, X)
+    assert np.all(np.abs(B @ X[:, :2]) == 0.0)
+    assert w[0] == 1.0 / (1e-28 * 2.0)
+    assert w[1] == 1.0 / (1e-28 * 18.0)
+    r = B.toarray() @ X[:, 2]
+    assert w[2] == 1.0 / float(r @ r)
