@@ -1659,33 +1659,50 @@ struct Engine : bamg_ctx {
             }
             T* a = lv.V;
             T* b = sweep_tmp;
+            // T_l's rows from its ELL-9 copy where B_l's come from one too
+            const bool t9 = es.ef == EF_ELL9 && lv.Tm.cci;
+            const int* tec = t9 ? lv.Tm.cci : nullptr;
+            const T* tev = t9 ? (const T*)lv.Tm.cv : nullptr;
+            const int teld = t9 ? lv.Tm.cld : 0;
+            auto teft = [&](auto&& go) {
+                if (t9) go(std::integral_constant<int, EF_ELL9>{});
+                else go(std::integral_constant<int, EF_CSR>{});
+            };
             ef_dispatch(es.ef, [&](auto efc) {
                 constexpr int EF = decltype(efc)::value;
-                auto relax = VS == 4 ? k_eig_relax<T, T, 4, EF>
-                           : VS == 8 ? k_eig_relax<T, T, 8, EF> : k_eig_relax<T, T, 12, EF>;
-                for (int k = 0; k < o.nu_setup; ++k) {
-                    if (mcgs) {      // in place, colour by colour
-                        for (int cc = 0; cc < ncol; ++cc)
-                            LAUNCH(relax, nblk(rows), BAMG_BLK, s, rows, (const ChainGeo*)lv.dgeo, lv.ncont,
-                                   (const int*)nvc, KV, lv.B.rp, lv.B.ci, (const T*)lv.B.v, es.c, es.v, es.ld,
-                                   lv.Tm.rp, lv.Tm.ci, (const T*)lv.Tm.v, (const double*)lam, (const int*)kind,
-                                   o.gs_omega, cc, (const T*)a, a);
-                        continue;
+                teft([&](auto eftc) {
+                    constexpr int EFT = EF == EF_ELL9 ? decltype(eftc)::value : EF_CSR;
+                    auto relax = VS == 4 ? k_eig_relax<T, T, 4, EF, EFT>
+                               : VS == 8 ? k_eig_relax<T, T, 8, EF, EFT> : k_eig_relax<T, T, 12, EF, EFT>;
+                    for (int k = 0; k < o.nu_setup; ++k) {
+                        if (mcgs) {      // in place, colour by colour
+                            for (int cc = 0; cc < ncol; ++cc)
+                                LAUNCH(relax, nblk(rows), BAMG_BLK, s, rows, (const ChainGeo*)lv.dgeo, lv.ncont,
+                                       (const int*)nvc, KV, lv.B.rp, lv.B.ci, (const T*)lv.B.v, es.c, es.v, es.ld,
+                                       lv.Tm.rp, lv.Tm.ci, (const T*)lv.Tm.v, tec, tev, teld, (const double*)lam,
+                                       (const int*)kind, o.gs_omega, cc, (const T*)a, a);
+                            continue;
+                        }
+                        LAUNCH(relax, nblk(rows), BAMG_BLK, s, rows, (const ChainGeo*)lv.dgeo, lv.ncont,
+                               (const int*)nvc, KV, lv.B.rp, lv.B.ci, (const T*)lv.B.v, es.c, es.v, es.ld, lv.Tm.rp,
+                               lv.Tm.ci, (const T*)lv.Tm.v, tec, tev, teld, (const double*)lam, (const int*)kind,
+                               o.omega, -1, (const T*)a, b);
+                        std::swap(a, b);
                     }
-                    LAUNCH(relax, nblk(rows), BAMG_BLK, s, rows, (const ChainGeo*)lv.dgeo, lv.ncont, (const int*)nvc,
-                           KV, lv.B.rp, lv.B.ci, (const T*)lv.B.v, es.c, es.v, es.ld, lv.Tm.rp, lv.Tm.ci,
-                           (const T*)lv.Tm.v, (const double*)lam, (const int*)kind, o.omega, -1, (const T*)a, b);
-                    std::swap(a, b);
-                }
+                });
             });
             if (a != lv.V) HIPCHK(hipMemcpyAsync(lv.V, a, sizeof(T) * tot, hipMemcpyDeviceToDevice, s));
             if (nvmax > 1) {
                 ef_dispatch(es.ef, [&](auto efc) {
-                    hipLaunchKernelGGL((k_rayleigh_partial<T, T, decltype(efc)::value>), dim3(lv.cnp, lv.ncont),
-                                       dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo, VS, KV, (const int*)nentc,
-                                       (const int*)ent_col, (const int*)kind, lv.B.rp, lv.B.ci, (const T*)lv.B.v, es.c,
-                                       es.v, es.ld, lv.Tm.rp, lv.Tm.ci, (const T*)lv.Tm.v, (const T*)lv.V, CN_ROWS,
-                                       part);
+                    constexpr int EF = decltype(efc)::value;
+                    teft([&](auto eftc) {
+                        constexpr int EFT = EF == EF_ELL9 ? decltype(eftc)::value : EF_CSR;
+                        hipLaunchKernelGGL((k_rayleigh_partial<T, T, EF, EFT>), dim3(lv.cnp, lv.ncont),
+                                           dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo, VS, KV, (const int*)nentc,
+                                           (const int*)ent_col, (const int*)kind, lv.B.rp, lv.B.ci, (const T*)lv.B.v,
+                                           es.c, es.v, es.ld, lv.Tm.rp, lv.Tm.ci, (const T*)lv.Tm.v, tec, tev, teld,
+                                           (const T*)lv.V, CN_ROWS, part);
+                    });
                 });
                 hipLaunchKernelGGL(k_rayleigh_final, dim3(KV, lv.ncont), dim3(BAMG_BLK), 0, s, (const ChainGeo*)lv.dgeo,
                                    CN_ROWS, lv.cnp, KV,

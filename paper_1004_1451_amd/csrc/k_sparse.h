@@ -1576,22 +1576,23 @@ k_ell9c_to_csr2(int nc, const int* __restrict__ bcc, const MV* __restrict__ bcv,
 // columns are relaxed and the others copied.  kind[c]: 0 real column with
 // real lam, 1 / 2 real / imaginary part of a complex pair x = V_c + i V_{c+1}
 // (lam complex; both columns of a pair form (B - lam T) x, each keeps its own
-// part); D_lam = diag(B) - lam diag(T).  T == identity when trp is null.
-// Column 0 (the null-vector approximation) has lam = 0.  Products are added
-// in CSR order in FP64.  colour >= 0: one colour of a multicolour
-// Gauss-Seidel sweep (k_mcgs.h), in place (Y == X), other rows untouched.
-template <typename T, typename M, int VP, int EF>
-__global__ void __launch_bounds__(BAMG_BLK)
-k_eig_relax(int n, const ChainGeo* __restrict__ geo, int nch, const int* __restrict__ nvc, int KV,
-            const int* __restrict__ brp, const int* __restrict__ bci, const M* __restrict__ bv,
-            const int* __restrict__ beci, const M* __restrict__ bev, int beld,
-            const int* __restrict__ trp, const int* __restrict__ tci, const M* __restrict__ tv,
-            const double* __restrict__ lamall, const int* __restrict__ kindall, double omega, int colour,
-            const T* X, T* Y) {
-    static_assert(VP % 4 == 0, "row stride must be a multiple of 4");
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
-    if (i >= n) return;
-    const int ch = find_chain(geo, nch, i);
+// part); D_lam = diag(B) - lam diag(T).  T == identity when trp and teci
+// are null; T's rows come from the storage EFT names (its ELL-9 copy on the
+// coarse grid levels).  Column 0 (the null-vector approximation) has lam = 0.
+// Products are added in CSR order in FP64 (an ELL copy adds its padding
+// (i, 0) as zeros).  colour >= 0: one colour of a multicolour Gauss-Seidel
+// sweep (k_mcgs.h), in place (Y == X), other rows untouched.  Row i of
+// chain ch here; k_eig_relax below is the launch.
+template <typename T, typename M, int VP, int EF, int EFT>
+__device__ __forceinline__ void eig_relax_row(int i, int ch, const ChainGeo* __restrict__ geo,
+                                              const int* __restrict__ nvc, int KV, const int* __restrict__ brp,
+                                              const int* __restrict__ bci, const M* __restrict__ bv,
+                                              const int* __restrict__ beci, const M* __restrict__ bev, int beld,
+                                              const int* __restrict__ trp, const int* __restrict__ tci,
+                                              const M* __restrict__ tv, const int* __restrict__ teci,
+                                              const M* __restrict__ tev, int teld, const double* __restrict__ lamall,
+                                              const int* __restrict__ kindall, double omega, int colour, const T* X,
+                                              T* Y) {
     if (colour >= 0 && point_colour(geo[ch], i - geo[ch].off) != colour) return;
     const int nv = nvc[ch];
     auto load = [&](int row, T (&x)[VP]) {
@@ -1601,7 +1602,7 @@ k_eig_relax(int n, const ChainGeo* __restrict__ geo, int nch, const int* __restr
     double bs[VP], ts[VP];
 #pragma unroll
     for (int c = 0; c < VP; ++c) { bs[c] = 0.0; ts[c] = 0.0; }
-    double bd = 0, td = trp ? 0.0 : 1.0;
+    double bd = 0, td = (trp || teci) ? 0.0 : 1.0;
     row_entries<EF, M>(i, brp, bci, bv, beci, bev, beld, [&](int j, M bvj) {
         const double b = (double)bvj;
         if (j == i && b != 0.0) bd = b;        // not the ELL padding (i, 0)
@@ -1612,16 +1613,15 @@ k_eig_relax(int n, const ChainGeo* __restrict__ geo, int nch, const int* __restr
     });
     T xo[VP];
     load(i, xo);
-    if (trp) {
-        for (int p = trp[i]; p < trp[i + 1]; ++p) {
-            const int j = tci[p];
-            const double t = (double)tv[p];
-            if (j == i) td = t;
+    if (trp || teci) {
+        row_entries<EFT, M>(i, trp, tci, tv, teci, tev, teld, [&](int j, M tvj) {
+            const double t = (double)tvj;
+            if (j == i && t != 0.0) td = t;    // not an ELL padding (i, 0)
             T x[VP];
             load(j, x);
 #pragma unroll
             for (int c = 0; c < VP; ++c) ts[c] += t * (double)x[c];
-        }
+        });
     } else {
 #pragma unroll
         for (int c = 0; c < VP; ++c) ts[c] = (double)xo[c];
@@ -1657,18 +1657,45 @@ k_eig_relax(int n, const ChainGeo* __restrict__ geo, int nch, const int* __restr
     for (int k = 0; k < VP; k += 4) VecIO<T, 4>::st(y + k, out + k);
 }
 
+// One thread per row; a workgroup whose rows lie in one chain passes the
+// chain as a workgroup-uniform value, so its kinds and eigenvalues are
+// scalar loads.
+template <typename T, typename M, int VP, int EF, int EFT = EF_CSR>
+__global__ void __launch_bounds__(BAMG_BLK)
+k_eig_relax(int n, const ChainGeo* __restrict__ geo, int nch, const int* __restrict__ nvc, int KV,
+            const int* __restrict__ brp, const int* __restrict__ bci, const M* __restrict__ bv,
+            const int* __restrict__ beci, const M* __restrict__ bev, int beld,
+            const int* __restrict__ trp, const int* __restrict__ tci, const M* __restrict__ tv,
+            const int* __restrict__ teci, const M* __restrict__ tev, int teld,
+            const double* __restrict__ lamall, const int* __restrict__ kindall, double omega, int colour,
+            const T* X, T* Y) {
+    static_assert(VP % 4 == 0, "row stride must be a multiple of 4");
+    const int b0 = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK;
+    const int i = b0 + threadIdx.x;
+    if (i >= n) return;
+    const int cf = find_chain(geo, nch, b0), cl = nch == 1 ? cf : find_chain(geo, nch, min(b0 + BAMG_BLK - 1, n - 1));
+    if (cf == cl)                                // the whole workgroup in one chain
+        eig_relax_row<T, M, VP, EF, EFT>(i, __builtin_amdgcn_readfirstlane(cf), geo, nvc, KV, brp, bci, bv, beci, bev,
+                                         beld, trp, tci, tv, teci, tev, teld, lamall, kindall, omega, colour, X, Y);
+    else
+        eig_relax_row<T, M, VP, EF, EFT>(i, find_chain(geo, nch, i), geo, nvc, KV, brp, bci, bv, beci, bev, beld,
+                                         trp, tci, tv, teci, tev, teld, lamall, kindall, omega, colour, X, Y);
+}
+
 // Rayleigh quotient partials, per chain (blockIdx.y) and row chunk of
 // seg_rows (blockIdx.x): for entry e (first column ent_col[e]; a pair uses
 // two) the sums x^H B x and x^H T x (re, im).  Thread layout: nent slots per
 // row (thread t: row t / nent, entry t % nent), then one thread per entry adds
-// the per-thread sums in thread order -> part[chain][chunk][entry][4].
-template <typename T, typename M, int EF>
+// the per-thread sums in thread order -> part[chain][chunk][entry][4].  T's
+// rows come from the storage EFT names (identity when trp and teci are null).
+template <typename T, typename M, int EF, int EFT = EF_CSR>
 __global__ void __launch_bounds__(BAMG_BLK)
 k_rayleigh_partial(const ChainGeo* __restrict__ geo, int R, int KV, const int* __restrict__ nentc,
                    const int* __restrict__ ent_colall, const int* __restrict__ kindall,
                    const int* __restrict__ brp, const int* __restrict__ bci, const M* __restrict__ bv,
                    const int* __restrict__ beci, const M* __restrict__ bev, int beld,
                    const int* __restrict__ trp, const int* __restrict__ tci, const M* __restrict__ tv,
+                   const int* __restrict__ teci, const M* __restrict__ tev, int teld,
                    const T* __restrict__ X, int seg_rows, double* __restrict__ part) {
     __shared__ double sh[4][BAMG_BLK];
     const int chn = blockIdx.y;
@@ -1689,13 +1716,12 @@ k_rayleigh_partial(const ChainGeo* __restrict__ geo, int R, int KV, const int* _
                 br += b * (double)X[(size_t)j * R + c];
                 if (pair) bi += b * (double)X[(size_t)j * R + c + 1];
             });
-            if (trp) {
-                for (int p = trp[i]; p < trp[i + 1]; ++p) {
-                    const int j = tci[p];
-                    const double tq = (double)tv[p];
+            if (trp || teci) {
+                row_entries<EFT, M>(i, trp, tci, tv, teci, tev, teld, [&](int j, M tvj) {
+                    const double tq = (double)tvj;
                     tr += tq * (double)X[(size_t)j * R + c];
                     if (pair) ti += tq * (double)X[(size_t)j * R + c + 1];
-                }
+                });
             } else {
                 tr = xr; ti = xi;
             }
