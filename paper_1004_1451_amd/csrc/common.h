@@ -203,6 +203,18 @@ __device__ __forceinline__ int find_chain(const ChainGeo* __restrict__ g, int nc
     return lo;
 }
 
+// f(chain of row i) for a row i of a workgroup whose rows are b0 .. b1
+// (b0 <= i <= b1).  When those rows lie in one chain (the usual case) the
+// chain is passed as a workgroup-uniform value, so the per-chain records f
+// reads are scalar loads rather than one vector load per lane.
+template <typename F>
+__device__ __forceinline__ auto with_chain(const ChainGeo* __restrict__ g, int nch, int b0, int b1, int i, F&& f) {
+    const int cf = find_chain(g, nch, b0);
+    const int cl = nch == 1 ? cf : find_chain(g, nch, b1);
+    if (cf == cl) return f(__builtin_amdgcn_readfirstlane(cf));
+    return f(find_chain(g, nch, i));
+}
+
 // Colours of the multicolour Gauss-Seidel relaxation: along one grid
 // direction of length m the positions alternate between colours 0 and 1, and
 // a periodic direction of odd length gives its last position colour 2, so

@@ -534,9 +534,11 @@ __global__ void k_restrict_box(int nc, const ChainGeo* __restrict__ geoc, const 
     if (!tile_active(RowMask{geoc, nch, act}, tile, BAMG_BLK, 1, nc)) return;
     int I = tile * BAMG_BLK + threadIdx.x;
     if (I >= nc) return;
-    const int ch = find_chain(geoc, nch, I);
-    const ChainGeo gc = geoc[ch];
-    const ChainGeo gf = geof[ch];
+    struct G2 { ChainGeo c, f; };
+    const G2 gg = with_chain(geoc, nch, tile * BAMG_BLK, min(tile * BAMG_BLK + BAMG_BLK - 1, nc - 1), I,
+                             [&](int c) { return G2{geoc[c], geof[c]}; });
+    const ChainGeo& gc = gg.c;
+    const ChainGeo& gf = gg.f;
     const int lI = I - gc.off;
     const int A = (int)gc.dy.div((uint32_t)lI), Bq = lI - A * gc.ny;
     const unsigned m = qmask[I];
@@ -922,8 +924,9 @@ __device__ __forceinline__ void ls_gram(int i, LsPoint& P, int valid, int Ru, in
         if (ld % 4 == 0) {
             // four columns per 16-byte load (rows are 4-aligned), CH columns
             // of the point's and its slots' rows loaded together before their
-            // sums; same order
-            constexpr int CH = sizeof(T) == 4 ? 12 : 8;
+            // sums; same order.  Eight columns keep the kernel within 168
+            // registers (three wavefronts per SIMD; twelve needed 196, two)
+            constexpr int CH = 8;
             for (int k0 = 0; k0 < nk; k0 += CH) {
                 T xi[CH], xs4[NS][CH];
                 double wk[CH];
@@ -1199,10 +1202,9 @@ k_ls_fit(int n, const ChainGeo* __restrict__ geo, int nch, int Ru, int use_v, co
          int caliber, int* __restrict__ pc, MP* __restrict__ pv, T* __restrict__ inject,
          unsigned char* __restrict__ jcnt, const int* __restrict__ brp, const int* __restrict__ bci,
          const M* __restrict__ bv, float* __restrict__ feat_out, float* __restrict__ slotw_out) {
-    const int t = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    const int b0 = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK, t = b0 + threadIdx.x;
     if (t >= n) return;
-    const int ch = find_chain(geo, nch, t);
-    const ChainGeo g = geo[ch];
+    const ChainGeo g = with_chain(geo, nch, b0, min(b0 + BAMG_BLK - 1, n - 1), t, [&](int c) { return geo[c]; });
     // Thread t takes a point of its own grid row: the fine columns first,
     // then the coarse ones, so a wavefront's lanes mostly take the same
     // branch (rows with C points: F points, then C points; the other rows:
@@ -1238,7 +1240,11 @@ k_ls_fit(int n, const ChainGeo* __restrict__ geo, int nch, int Ru, int use_v, co
         return;
     }
     LsPoint P;
-    ls_point<T>(i, g, ia, ib, Ru, use_v ? nvc[ch] : 0, VS, U, V, wall + (size_t)ch * WS, caliber, P);
+    // the chain's weights as workgroup-uniform loads where the rows allow
+    with_chain(geo, nch, b0, min(b0 + BAMG_BLK - 1, n - 1), t, [&](int c) {
+        ls_point<T>(i, g, ia, ib, Ru, use_v ? nvc[c] : 0, VS, U, V, wall + (size_t)c * WS, caliber, P);
+        return 0;
+    });
     const int cnt = write_prow<MP>(i, P.J, P.sc, P.p, pc, pv);
     if (jcnt) jcnt[i] = (unsigned char)cnt;
     if (feat_out) {
@@ -1259,11 +1265,14 @@ template <typename MQ>
 __global__ void k_build_q(int nc, const ChainGeo* __restrict__ geoc, const ChainGeo* __restrict__ geof, int nch,
                           const int* __restrict__ pc, int* __restrict__ qc, MQ* __restrict__ qv,
                           unsigned short* __restrict__ qmask) {
-    int I = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK + threadIdx.x;
+    const int b0 = xcd_tile(blockIdx.x, gridDim.x) * BAMG_BLK;
+    int I = b0 + threadIdx.x;
     if (I >= nc) return;
-    const int ch = find_chain(geoc, nch, I);
-    const ChainGeo gc = geoc[ch];
-    const ChainGeo g = geof[ch];
+    struct G2 { ChainGeo c, f; };
+    const G2 gg = with_chain(geoc, nch, b0, min(b0 + BAMG_BLK - 1, nc - 1), I,
+                             [&](int c) { return G2{geoc[c], geof[c]}; });
+    const ChainGeo& gc = gg.c;
+    const ChainGeo& g = gg.f;
     const int lI = I - gc.off;
     int A = (int)gc.dy.div((uint32_t)lI), Bq = lI - A * gc.ny;
     int fa = grid_fine_pos(A, g.nx, g.periodic), fb = grid_fine_pos(Bq, g.ny, g.periodic);
@@ -1499,8 +1508,10 @@ k_galerkin_bt(int nc, const ChainGeo* __restrict__ geoc, int nch, const int* __r
     for (int u = 0; u < 9; ++u) { tb[u] = 0; tt[u] = 0; }
     unsigned mb = 0, mt = 0;
     int Ia = 0, Ib = 0, ncx = 1, ncy = 1, periodic = 0, goff = 0;
+    const int b0 = xcd_tile(blockIdx.x, gridDim.x) * GR;
+    const ChainGeo g = with_chain(geoc, nch, b0, min(b0 + GR - 1, nc - 1), min(I, nc - 1),
+                                  [&](int c) { return geoc[c]; });
     if (I < nc) {
-        const ChainGeo g = geoc[find_chain(geoc, nch, I)];
         ncx = g.nx; ncy = g.ny; periodic = g.periodic; goff = g.off;
         const int lI = I - g.off;
         Ia = (int)g.dy.div((uint32_t)lI); Ib = lI - Ia * ncy;
