@@ -74,6 +74,11 @@ inline int nblk(long long n) { return (int)std::max<long long>(1, (n + BAMG_BLK 
 // a large chain fills the chip and a chain's summation order does not depend
 // on the other chains of its batch.
 constexpr int SEG_ROWS = 1024;
+// Coarse grid levels of at most this many rows take the prolongation and the
+// first post-smoothing sweep of the cycle in one pass (measured on the C2
+// hierarchy: 5.5-5.8 us against 8.0-8.3 us for the two launches at 16K and
+// 66K rows, but 11.7 against 8.6 us at 263K rows).
+constexpr int FUSE_ROWS = 1 << 17;
 // The TV-weight and Rayleigh partials do a sparse product per (row, column)
 // on top of the sum: shorter chunks keep many workgroups in flight.
 constexpr int CN_ROWS = 256;
@@ -103,12 +108,15 @@ static void ef_dispatch(int ef, F&& f) {
     else f(std::integral_constant<int, EF_CSR>{});
 }
 
-// Calls f(std::integral_constant<int, K>) with K the multiple of 8 (8 .. 64)
-// that covers nb finished basis vectors: the register width of the
-// Gram-Schmidt passes.
+// Calls f(std::integral_constant<int, K>) with K = 1, 2, 4 or the multiple
+// of 8 (8 .. 64), the smallest that covers nb finished basis vectors: the
+// register width of the Gram-Schmidt passes (their sums do not depend on K).
 template <typename F>
 static void gs_dispatch(int nb, F&& f) {
-    switch ((std::max(nb, 1) + 7) / 8) {
+    if (nb <= 1) { f(std::integral_constant<int, 1>{}); return; }
+    if (nb <= 2) { f(std::integral_constant<int, 2>{}); return; }
+    if (nb <= 4) { f(std::integral_constant<int, 4>{}); return; }
+    switch ((nb + 7) / 8) {
         case 1: f(std::integral_constant<int, 8>{}); break;
         case 2: f(std::integral_constant<int, 16>{}); break;
         case 3: f(std::integral_constant<int, 24>{}); break;
@@ -791,8 +799,9 @@ struct Engine : bamg_ctx {
 
     void alloc_globals() {
         if (MIXED) {
-            b0rp = A.alloc<int>(n + 1);
-            b0ci = A.alloc<int>(L[0].B.cap);
+            // the FP32 and FP64 forms of B_0 share one structure
+            b0rp = L[0].B.rp;
+            b0ci = L[0].B.ci;
             b0v = A.alloc<double>(L[0].B.cap);
         } else {
             b0rp = L[0].B.rp;
@@ -975,50 +984,42 @@ struct Engine : bamg_ctx {
         LAUNCH(k_check_a, nblk(n), BAMG_BLK, s, (int)n, rp, ci, val, (const ChainGeo*)lv.dgeo, lv.nch, nnzA, colsum,
                itmp, err);
         LAUNCH(k_check_colsum, nblk(n), BAMG_BLK, s, (int)n, colsum, err);
-        int e = get1(err);
+        // the row counts are scanned before the flags are read (a scan of
+        // counts touches no memory they index), so one read-back brings both
+        // the flags and nnz(B_0)
+        scan((int)n, itmp, b0rp);
+        LAUNCH(k_copy_int, 1, BAMG_WAVE, s, (const int*)(b0rp + n), err + 1);
+        const std::vector<int> chk = getn(err, 2);
+        const int e = chk[0];
         if (e & ERR_RANGE)
             fail(BAMG_EINVAL, "CSR of A: row_ptr not monotone, column out of range or outside its chain, or columns "
                               "not strictly ascending");
         if (e & ERR_NEG) fail(BAMG_ENOTSTOCH, "A has a negative, non-finite or > 1 entry");
         if (e & ERR_COLSUM) fail(BAMG_ENOTSTOCH, "a column of A does not sum to 1 within 1e-12");
         if (e & ERR_WIDE) fail(BAMG_EUNSUPPORTED, "A joins states farther apart than the 3x3 grid box");
-        scan((int)n, itmp, b0rp);
-        nnz0 = get1(b0rp + n);
+        nnz0 = chk[1];
+        // the ELL-4 copy of B_0 (and of its FP64 values in the mixed form)
+        // for the level-0 sweeps, the cycle's level-0 residual and the outer
+        // SpMV, written by the same pass when every row may have at most 4
+        // entries (BAMG_SWEEP_ELL=0 turns it off)
+        const char* ee = getenv("BAMG_SWEEP_ELL");
+        const bool ell = !(ee && ee[0] == '0') && nnz0 <= 4LL * lv.rows;
+        int* eci = ell ? A.alloc<int>((size_t)lv.rows * 4) : nullptr;
+        T* ev = ell ? A.alloc<T>((size_t)lv.rows * 4) : nullptr;
+        double* ev64 = ell ? (MIXED ? A.alloc<double>((size_t)lv.rows * 4) : (double*)ev) : nullptr;
         T* lo = MIXED ? lv.B.v : nullptr;
         T* dlo = MIXED ? lv.dinv : nullptr;
         double* dinv64 = MIXED ? A.alloc<double>(n) : (double*)lv.dinv;
-        LAUNCH(k_build_b<T>, nblk(n), BAMG_BLK, s, (int)n, rp, ci, val, b0rp, b0ci, b0v, lo, o.omega, dinv64, dlo, err);
-        if (MIXED) {
-            HIPCHK(hipMemcpyAsync(lv.B.rp, b0rp, sizeof(int) * (n + 1), hipMemcpyDeviceToDevice, s));
-            HIPCHK(hipMemcpyAsync(lv.B.ci, b0ci, sizeof(int) * nnz0, hipMemcpyDeviceToDevice, s));
-        }
-        e = get1(err);
-        if (e & ERR_ZERODIAG) fail(BAMG_EZERODIAG, "b_ii <= 0 on the finest level");
-    }
-
-    // ELL-4 copy of B_0 (and of its FP64 values in the mixed form) for the
-    // level-0 sweeps, the cycle's level-0 residual and the outer SpMV when
-    // every row has at most 4 entries (BAMG_SWEEP_ELL=0 turns it off).
-    void build_ell0() {
-        const char* e = getenv("BAMG_SWEEP_ELL");
-        if (e && e[0] == '0') return;
-        auto& lv = L[0];
-        const int rows = lv.rows;
-        if (nnz0 > 4LL * rows) return;
-        int* eci = A.alloc<int>((size_t)rows * 4);
-        T* ev = A.alloc<T>((size_t)rows * 4);
-        double* ev64 = MIXED ? A.alloc<double>((size_t)rows * 4) : (double*)ev;
         zero(err, sizeof(int) * 4);
-        if (MIXED)   // one pass over the FP64 rows: the columns, both value copies
-            LAUNCH(k_csr_to_ell4_mixed, nblk(rows), BAMG_BLK, s, rows, (const int*)b0rp, (const int*)b0ci,
-                   (const double*)b0v, eci, (float*)ev, ev64, err);
-        else
-            LAUNCH((k_csr_to_ell4<T>), nblk(rows), BAMG_BLK, s, rows, (const int*)lv.B.rp, (const int*)lv.B.ci,
-                   (const T*)lv.B.v, eci, ev, err);
-        if (get1(err)) return;
-        lv.B.eci = eci;
-        lv.B.ev = ev;
-        b0ev = ev64;
+        LAUNCH(k_build_b<T>, nblk(n), BAMG_BLK, s, (int)n, rp, ci, val, b0rp, b0ci, b0v, lo, o.omega, dinv64, dlo, eci,
+               MIXED ? ev : (T*)nullptr, ev64, err);
+        const int e2 = get1(err);
+        if (e2 & ERR_ZERODIAG) fail(BAMG_EZERODIAG, "b_ii <= 0 on the finest level");
+        if (ell && !(e2 & ERR_ELL)) {
+            lv.B.eci = eci;
+            lv.B.ev = ev;
+            b0ev = ev64;
+        }
     }
 
     // -------------------------------------------------------------- setup steps
@@ -1231,6 +1232,14 @@ struct Engine : bamg_ctx {
                            use_v, (const int*)nvc, WS,
                            (const double*)part, wts);
         HIPCHK(hipGetLastError());
+    }
+
+    // BAMG_CYCLE_FUSE=0 in the environment: the cycle takes the
+    // prolongation and the first post-smoothing sweep of a small coarse grid
+    // level as separate launches (the fused pass computes the same bits).
+    static bool cycle_fuse_on() {
+        const char* e = getenv("BAMG_CYCLE_FUSE");
+        return !(e && e[0] == '0');
     }
 
     // BAMG_SWEEP_ELL=0 in the environment: kernels read the coarse grid
@@ -1593,9 +1602,15 @@ struct Engine : bamg_ctx {
             // the start vector is basis column 0 (no H entry), then t1 = T v_0
             arnoldi_start();
             hipLaunchKernelGGL(k_cz_tv<T>, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, 0, (const double*)Vb, t1);
+            const dim3 gw2(ceil_div(maxnL, 2), nch);
             for (int j = 0; j < AMmax; ++j) {
-                hipLaunchKernelGGL(k_cz_arn_gemv, gw, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j, (const double*)Wp,
-                                   (const double*)t1, Vb);
+                // the mixed form multiplies by its FP32 copy of W (half the bytes)
+                if (MIXED)
+                    hipLaunchKernelGGL(k_cz_arn_gemv_f32, gw2, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j,
+                                       (const float*)Wfp, (const double*)t1, Vb);
+                else
+                    hipLaunchKernelGGL(k_cz_arn_gemv, gw, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j,
+                                       (const double*)Wp, (const double*)t1, Vb);
                 HIPCHK(hipGetLastError());
                 arnoldi_orthogonalize(j);
             }
@@ -2041,7 +2056,6 @@ struct Engine : bamg_ctx {
         allocate(nnzA);
         if (nch > 1) reorder_input(rp, ci, val, nnzA);
         build_b0(rp, ci, val, nnzA);
-        build_ell0();
         if (unstructured) check_symmetric();
         check_colours(0);
         const bool prof = o.profile != 0;
@@ -2232,12 +2246,24 @@ struct Engine : bamg_ctx {
                    (const ChainGeo*)lv.dgeo, c.nch, (const unsigned short*)lv.qmask, (const unsigned char*)lv.jcnt,
                    (const T*)lv.r, c.f, (const int*)cmask);
         vcycle(l + 1);
-        LAUNCH((k_prolong_add<T, T>), nb, BAMG_BLK, s, rows, lv.pc, (const T*)lv.pv, (const T*)c.e, cur, mk);
+        int k = 0;
+        if (lv.B.cci && rows <= FUSE_ROWS && !mcgs && o.nu_post >= 1 && cycle_fuse_on()) {
+            // the prolongation and the first post-smoothing sweep in one pass
+            // (on small levels, where a launch costs more than recomputing
+            // the neighbours' prolongation)
+            LAUNCH((k_prolong_sweep_c9<T, T>), nb, BAMG_BLK, s, rows, lv.rows, (const int*)lv.B.cci,
+                   (const T*)lv.B.cv, (const T*)lv.dinv, lv.pc, (const T*)lv.pv, (const T*)c.e, (const T*)cur,
+                   (const T*)lv.f, oth, mk);
+            std::swap(cur, oth);
+            k = 1;
+        } else {
+            LAUNCH((k_prolong_add<T, T>), nb, BAMG_BLK, s, rows, lv.pc, (const T*)lv.pv, (const T*)c.e, cur, mk);
+        }
         if (mcgs) {
             gs_sweeps(o.nu_post);
             return;
         }
-        for (int k = 0; k < o.nu_post; ++k) {
+        for (; k < o.nu_post; ++k) {
             cycle_sweep(lv, rows, nb, cur, oth, mk);
             std::swap(cur, oth);
         }
@@ -3404,7 +3430,8 @@ int bamg_relax(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const 
         double* bv = A.alloc<double>(nnzB);
         double* dinv = A.alloc<double>(N);
         LAUNCH(k_build_b<double>, nb, BAMG_BLK, s, N, row_ptr, col_idx, val, (const int*)brp, bci, bv,
-               (double*)nullptr, omega, dinv, (double*)nullptr, err);
+               (double*)nullptr, omega, dinv, (double*)nullptr, (int*)nullptr, (double*)nullptr, (double*)nullptr,
+               err);
         HIPCHK(hipMemcpyAsync(&e, err, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (e & ERR_ZERODIAG) fail(BAMG_EZERODIAG, "b_ii <= 0");

@@ -1476,6 +1476,79 @@ k_cz_arn_gemv(const CoarseDesc* __restrict__ cd, int j, const double* __restrict
     }
 }
 
+// The same product from the FP32 copy of W (mixed precision): the vector
+// stays FP64 and every product and sum is FP64, so the only change from
+// the FP64 form is W rounded to FP32.  One workgroup per pair of rows, so
+// that each load of w serves both and every wavefront has its loads of a
+// quarter of the row in flight at once: thread t sums the column groups
+// 4q .. 4q+3, q = t, t + BAMG_BLK, ..., in column order (thread t < n mod 4
+// also tail column 4 (n / 4) + t), then each wavefront's sum, then the four
+// in order.  The last row of an odd n pairs with itself (read twice, stored
+// once).
+__global__ void __launch_bounds__(BAMG_BLK)
+k_cz_arn_gemv_f32(const CoarseDesc* __restrict__ cd, int j, const float* __restrict__ Wf,
+                  const double* __restrict__ w, double* __restrict__ Vb) {
+    __shared__ double red[BAMG_BLK / BAMG_WAVE][2];
+    const CoarseDesc d = cd[blockIdx.y];
+    if (j >= d.am) return;
+    const float* W = Wf + d.wfoff;
+    const double* x = w + d.voff;
+    double* u = Vb + d.aoff + (size_t)(j + 1) * d.n;
+    const int t = threadIdx.x, lane = t % BAMG_WAVE, wv = t / BAMG_WAVE;
+    const int n4 = d.n / 4;
+    const bool v4 = (d.wfld & 3) == 0 &&
+                    ((reinterpret_cast<uintptr_t>(W) | reinterpret_cast<uintptr_t>(x)) & 15) == 0;
+    for (int r0 = 2 * blockIdx.x; r0 < d.n; r0 += 2 * gridDim.x) {
+        const int r1 = min(r0 + 1, d.n - 1);
+        const float* a0 = W + (size_t)r0 * d.wfld;
+        const float* a1 = W + (size_t)r1 * d.wfld;
+        double s0 = 0, s1 = 0;
+        if (v4) {
+            const float4* p4 = (const float4*)a0;
+            const float4* q4 = (const float4*)a1;
+            const double2* x2 = (const double2*)x;
+#pragma unroll 4
+            for (int q = t; q < n4; q += BAMG_BLK) {
+                const float4 p = p4[q], r = q4[q];
+                const double2 xa = x2[2 * q], xb = x2[2 * q + 1];
+                s0 += (double)p.x * xa.x;
+                s0 += (double)p.y * xa.y;
+                s0 += (double)p.z * xb.x;
+                s0 += (double)p.w * xb.y;
+                s1 += (double)r.x * xa.x;
+                s1 += (double)r.y * xa.y;
+                s1 += (double)r.z * xb.x;
+                s1 += (double)r.w * xb.y;
+            }
+        } else {
+            for (int q = t; q < n4; q += BAMG_BLK)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const double xv = x[4 * q + e];
+                    s0 += (double)a0[4 * q + e] * xv;
+                    s1 += (double)a1[4 * q + e] * xv;
+                }
+        }
+        if (4 * n4 + t < d.n) {
+            const double xv = x[4 * n4 + t];
+            s0 += (double)a0[4 * n4 + t] * xv;
+            s1 += (double)a1[4 * n4 + t] * xv;
+        }
+        s0 = wave_sum(s0);
+        s1 = wave_sum(s1);
+        if (lane == 0) { red[wv][0] = s0; red[wv][1] = s1; }
+        __syncthreads();
+        if (t == 0) {
+            double b0 = 0, b1 = 0;
+#pragma unroll
+            for (int k = 0; k < BAMG_BLK / BAMG_WAVE; ++k) { b0 += red[k][0]; b1 += red[k][1]; }
+            u[r0] = b0;
+            if (r0 + 1 < d.n) u[r0 + 1] = b1;
+        }
+        __syncthreads();
+    }
+}
+
 // This block's sums of u^2 and u y (fixed order) into npart[(chain,
 // block) * 2 ..], for k_cz_arn_normalize.
 __device__ __forceinline__ void cz_norm_partials(double ss, double st, double* sh, double* sh2,

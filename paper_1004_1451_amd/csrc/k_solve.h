@@ -277,15 +277,21 @@ __global__ void k_seg_reduce_final(const ChainGeo* __restrict__ geo, int seg_row
 #define GS_CS (2 * GS_MAXB + 4)
 
 // Dots pass: <q_b, w> (b < nb), <v_nb, w>, <w, w> on a chunk of one chain.
-// K >= nb accumulators per thread (K a multiple of 8); grid (chunks, chains).
-// V_b starts at V + b ldv.  Every thread issues all K loads of a row
-// unconditionally (b >= nb re-reads v_nb, a cache hit) so that they are in
-// flight together; the sums b >= nb are never stored.
+// K >= nb accumulators per thread (1, 2, 4 or a multiple of 8); grid
+// (chunks, chains).  V_b starts at V + b ldv.  Every thread issues all K
+// loads of a row unconditionally (b >= nb re-reads v_nb, a cache hit) so that
+// they are in flight together; the sums b >= nb are never stored.  With
+// K <= 4 a thread loads GsRows<K>::U of its rows (i, i + BAMG_BLK, ...) before
+// the products, which it adds in row order as one row at a time would.
+template <int K>
+struct GsRows { static constexpr int U = K <= 2 ? 4 : K <= 4 ? 2 : 1; };
+
 template <int K>
 __global__ void __launch_bounds__(BAMG_BLK)
 k_gs_dots(const ChainGeo* __restrict__ geo, int seg_rows, int ldv, int nb, const int* __restrict__ act,
           const double* __restrict__ V, const double* __restrict__ w, double* __restrict__ part, int NDM) {
     __shared__ double red[(BAMG_BLK / BAMG_WAVE) * (GsRed<K>::KR + 2)];
+    constexpr int U = GsRows<K>::U;
     const ChainGeo g = geo[blockIdx.y];
     if (!act[blockIdx.y]) return;
     const int i0 = g.off + blockIdx.x * seg_rows, i1 = min(g.off + g.n, i0 + seg_rows);
@@ -295,17 +301,25 @@ k_gs_dots(const ChainGeo* __restrict__ geo, int seg_rows, int ldv, int nb, const
 #pragma unroll
     for (int b = 0; b < K; ++b) acc[b] = 0.0;
     double ey = 0.0, ex = 0.0;
-    for (int i = i0 + threadIdx.x; i < i1; i += BAMG_BLK) {
-        const double x = w[i];
-        double q[K];
+    for (int i = i0 + threadIdx.x; i < i1; i += U * BAMG_BLK) {
+        double x[U], q[U][K], yi[U];
 #pragma unroll
-        for (int b = 0; b < K; ++b) q[b] = (b < nb ? V + (size_t)b * ldv : y)[i];
-        const double yi = y[i];
+        for (int u = 0; u < U; ++u) {
+            const int r = i + u * BAMG_BLK < i1 ? i + u * BAMG_BLK : i;
+            x[u] = w[r];
+#pragma unroll
+            for (int b = 0; b < K; ++b) q[u][b] = (b < nb ? V + (size_t)b * ldv : y)[r];
+            yi[u] = y[r];
+        }
         __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the products
 #pragma unroll
-        for (int b = 0; b < K; ++b) acc[b] += q[b] * x;
-        ey += yi * x;
-        ex += x * x;
+        for (int u = 0; u < U; ++u) {
+            if (i + u * BAMG_BLK >= i1) break;
+#pragma unroll
+            for (int b = 0; b < K; ++b) acc[b] += q[u][b] * x[u];
+            ey += yi[u] * x[u];
+            ex += x[u] * x[u];
+        }
     }
     gs_store_partials<K>(acc, ey, ex, nb, part, NDM, red);
 }
@@ -317,7 +331,8 @@ k_gs_dots(const ChainGeo* __restrict__ geo, int seg_rows, int ldv, int nb, const
 // h q_nb) / nu into V_{nb+1}, then the dots of v_{nb+1}.  The q_b of a row
 // are loaded once into registers (K >= nb, all K loads issued together; b >=
 // nb re-reads v_nb with a zero coefficient, which leaves the sums unchanged)
-// for the updates and the dots; the coefficients sit in LDS.
+// for the updates and the dots, GsRows<K>::U rows at a time as in the dots
+// pass; the coefficients sit in LDS.
 template <int K>
 __global__ void __launch_bounds__(BAMG_BLK)
 k_gs_update(const ChainGeo* __restrict__ geo, int seg_rows, int ldv, int nb, const int* __restrict__ act,
@@ -342,25 +357,36 @@ k_gs_update(const ChainGeo* __restrict__ geo, int seg_rows, int ldv, int nb, con
 #pragma unroll
     for (int b = 0; b < K; ++b) acc[b] = 0.0;
     double ey = 0.0, ex = 0.0;
-    for (int i = i0 + threadIdx.x; i < i1; i += BAMG_BLK) {
-        double q[K];
+    constexpr int U = GsRows<K>::U;
+    for (int i = i0 + threadIdx.x; i < i1; i += U * BAMG_BLK) {
+        double q[U][K], tv[U], xv[U];
 #pragma unroll
-        for (int b = 0; b < K; ++b) q[b] = (b < nb ? V + (size_t)b * ldv : y)[i];
-        double t = y[i];
-        double x = w[i];
+        for (int u = 0; u < U; ++u) {
+            const int r = i + u * BAMG_BLK < i1 ? i + u * BAMG_BLK : i;
+#pragma unroll
+            for (int b = 0; b < K; ++b) q[u][b] = (b < nb ? V + (size_t)b * ldv : y)[r];
+            tv[u] = y[r];
+            xv[u] = w[r];
+        }
         __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the products
 #pragma unroll
-        for (int b = 0; b < K; ++b) t -= sa[b] * q[b];
-        t *= ia;
-        if (nb > 0) y[i] = t;
+        for (int u = 0; u < U; ++u) {
+            const int r = i + u * BAMG_BLK;
+            if (r >= i1) break;
+            double t = tv[u], x = xv[u];
 #pragma unroll
-        for (int b = 0; b < K; ++b) x -= sd[b] * q[b];
-        x = (x - hh * t) * inu;
-        xn[i] = x;
+            for (int b = 0; b < K; ++b) t -= sa[b] * q[u][b];
+            t *= ia;
+            if (nb > 0) y[r] = t;
 #pragma unroll
-        for (int b = 0; b < K; ++b) acc[b] += q[b] * x;
-        ey += t * x;
-        ex += x * x;
+            for (int b = 0; b < K; ++b) x -= sd[b] * q[u][b];
+            x = (x - hh * t) * inu;
+            xn[r] = x;
+#pragma unroll
+            for (int b = 0; b < K; ++b) acc[b] += q[u][b] * x;
+            ey += t * x;
+            ex += x * x;
+        }
     }
     gs_store_partials<K>(acc, ey, ex, nb, part, NDM, red);
 }

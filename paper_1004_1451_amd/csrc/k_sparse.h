@@ -17,6 +17,7 @@ enum : int {
     ERR_WIDE = 4,       // entry joins states farther apart than the 3x3 box
     ERR_COLSUM = 8,     // |column sum - 1| > 1e-12
     ERR_ZERODIAG = 16,  // b_ii <= 0
+    ERR_ELL = 32,       // a row of B_0 has more than 4 entries (no ELL-4 copy)
 };
 
 struct GridDev {
@@ -87,18 +88,28 @@ __global__ void k_check_colsum(int n, const double* __restrict__ colsum, int* __
     if (!(fabs(colsum[j] - 1.0) <= 1e-12)) atomicOr(err, ERR_COLSUM);
 }
 
-// Pass 2: write row i of B = I - A and dinv_i = omega / b_ii.
+// Pass 2: write row i of B = I - A and dinv_i = omega / b_ii.  With eci
+// set, also the row's ELL-4 copy: the columns in eci, padded with (i, 0) as
+// a CSR walk adds nothing for them, the FP64 values in ev64 and, with ev_lo
+// set, their roundings to M; a row of more than 4 entries sets ERR_ELL
+// instead (the copy is then not used).
 template <typename M>
 __global__ void k_build_b(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                           const double* __restrict__ v, const int* __restrict__ brp,
                           int* __restrict__ bci, double* __restrict__ bv, M* __restrict__ bv_lo,
                           double omega, double* __restrict__ dinv, M* __restrict__ dinv_lo,
+                          int* __restrict__ eci, M* __restrict__ ev_lo, double* __restrict__ ev64,
                           int* __restrict__ err) {
     int i = blockIdx.x * BAMG_BLK + threadIdx.x;
     if (i >= n) return;
     int q = brp[i];
     bool done = false;
     double diag = 1.0;
+    // the row's first four entries as written, for the ELL copy, in
+    // registers (slot u takes the entry whose index is u)
+    int ec[4] = {i, i, i, i};
+    double evv[4] = {0.0, 0.0, 0.0, 0.0};
+    int len = 0;
     // each entry written once, to the FP64 and (if asked) the low-precision
     // values together
     auto put = [&](int col, double val) {
@@ -106,6 +117,10 @@ __global__ void k_build_b(int n, const int* __restrict__ rp, const int* __restri
         bv[q] = val;
         if (bv_lo) bv_lo[q] = (M)val;
         ++q;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (u == len) { ec[u] = col; evv[u] = val; }
+        ++len;
     };
     const int p0 = rp[i], p1 = rp[i + 1];
     if (p1 - p0 <= 4) {
@@ -138,6 +153,16 @@ __global__ void k_build_b(int n, const int* __restrict__ rp, const int* __restri
     if (!(diag > 0.0)) atomicOr(err, ERR_ZERODIAG);
     dinv[i] = omega / diag;
     if (dinv_lo) dinv_lo[i] = (M)(omega / diag);
+    if (eci) {
+        if (len > 4) {
+            atomicOr(err, ERR_ELL);
+        } else {
+            *(int4*)(eci + (size_t)i * 4) = make_int4(ec[0], ec[1], ec[2], ec[3]);
+            ((double2*)(ev64 + (size_t)i * 4))[0] = make_double2(evv[0], evv[1]);
+            ((double2*)(ev64 + (size_t)i * 4))[1] = make_double2(evv[2], evv[3]);
+            if (ev_lo) Ell4Val<M>::st(ev_lo + (size_t)i * 4, evv);
+        }
+    }
 }
 
 // dinv_i = omega / b_ii for a coarse operator (diagonal always stored, since
@@ -325,30 +350,6 @@ k_spmv(int n, const int* __restrict__ rp, const int* __restrict__ ci, const M* _
 // over a row prefix n; CSR order, padded with (i, 0)), which the Galerkin
 // product writes directly: the one-row-per-thread cycle kernels load the 9
 // columns and values of their rows with coalesced, independent loads.
-
-// Both ELL-4 copies of the finest B in the mixed form from its FP64 CSR in
-// one pass: the shared column array, the FP64 values and their FP32
-// roundings (what the FP32 CSR copy holds); err = 1 when a row has more
-// than 4 entries (the copies are then not used).
-__global__ void k_csr_to_ell4_mixed(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                    const double* __restrict__ v, int* __restrict__ eci, float* __restrict__ ev,
-                                    double* __restrict__ ev64, int* __restrict__ err) {
-    const int i = blockIdx.x * BAMG_BLK + threadIdx.x;
-    if (i >= n) return;
-    const int p0 = rp[i], len = rp[i + 1] - p0;
-    if (len > 4) { *err = 1; return; }
-    int c[4];
-    double w[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        c[u] = u < len ? ci[p0 + u] : i;
-        w[u] = u < len ? v[p0 + u] : 0.0;
-    }
-    *(int4*)(eci + (size_t)i * 4) = make_int4(c[0], c[1], c[2], c[3]);
-    *(float4*)(ev + (size_t)i * 4) = make_float4((float)w[0], (float)w[1], (float)w[2], (float)w[3]);
-    ((double2*)(ev64 + (size_t)i * 4))[0] = make_double2(w[0], w[1]);
-    ((double2*)(ev64 + (size_t)i * 4))[1] = make_double2(w[2], w[3]);
-}
 
 // The multi-vector Jacobi sweep (k_sweep_v) on the column-major ELL-9 copy
 // of a coarse grid level (slot k of row i at k * ld + i): one thread per
@@ -578,6 +579,54 @@ __global__ void k_prolong_add(int n, const int* __restrict__ pc, const M* __rest
     for (int s = 0; s < 4; ++s)
         if (J[s] >= 0) acc += (T)w[s] * x[s];
     e[i] += acc;
+}
+
+// e_j + (P e_c)_j for row j, formed as k_prolong_add forms it.
+template <typename T, typename M>
+__device__ __forceinline__ T prolonged(int j, const int* __restrict__ pc, const M* __restrict__ pv,
+                                       const T* __restrict__ ec, const T* __restrict__ e) {
+    const int4 c4 = *(const int4*)(pc + (size_t)j * 4);
+    const int J[4] = {c4.x, c4.y, c4.z, c4.w};
+    M w[4];
+    Ell4Val<M>::ld(pv + (size_t)j * 4, w);
+    T x[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) x[s] = J[s] >= 0 ? ec[J[s]] : (T)0;
+    T acc = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        if (J[s] >= 0) acc += (T)w[s] * x[s];
+    return e[j] + acc;
+}
+
+// The prolongation and the first post-smoothing sweep of the cycle in one
+// pass on a coarse grid level (ELL-9 copy): Y = e' + D^-1 (f - B e') with
+// e' = e + P e_c formed for the row and for each of its nine columns on the
+// fly, so that e' is neither written nor read back.  The same bits as
+// k_prolong_add followed by k_sweep_c9; e itself is left unchanged.
+template <typename T, typename M>
+__global__ void __launch_bounds__(BAMG_BLK)
+k_prolong_sweep_c9(int n, int ld, const int* __restrict__ cci, const M* __restrict__ cv, const M* __restrict__ dinv,
+                   const int* __restrict__ pc, const M* __restrict__ pv, const T* __restrict__ ec,
+                   const T* __restrict__ e, const T* __restrict__ F, T* __restrict__ Y, RowMask mk) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (!tile_active(mk, tile, BAMG_BLK, 1, n)) return;
+    const int i = tile * BAMG_BLK + threadIdx.x;
+    if (i >= n) return;
+    int c[9];
+    M w[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) { c[k] = cci[(size_t)k * ld + i]; w[k] = cv[(size_t)k * ld + i]; }
+    const T d = (T)dinv[i];
+    const T f = F ? F[i] : (T)0;
+    const T xt = prolonged<T, M>(i, pc, pv, ec, e);
+    T x[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) x[k] = prolonged<T, M>(c[k], pc, pv, ec, e);
+    T acc = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc += (T)w[k] * x[k];
+    Y[i] = xt + d * (f - acc);
 }
 
 // V_f = P V_c on R interleaved columns (interpolation of the eigenvector

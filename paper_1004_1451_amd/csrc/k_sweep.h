@@ -148,11 +148,19 @@ template <> struct Ell4Val<float> {
     static __device__ __forceinline__ void ld(const float* p, float* w) {
         const float4 a = *(const float4*)p; w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
     }
+    // the four FP64 values rounded to FP32, one 16-byte store
+    static __device__ __forceinline__ void st(float* p, const double* w) {
+        *(float4*)p = make_float4((float)w[0], (float)w[1], (float)w[2], (float)w[3]);
+    }
 };
 template <> struct Ell4Val<double> {
     static __device__ __forceinline__ void ld(const double* p, double* w) {
         const double2 a = ((const double2*)p)[0], b = ((const double2*)p)[1];
         w[0] = a.x; w[1] = a.y; w[2] = b.x; w[3] = b.y;
+    }
+    static __device__ __forceinline__ void st(double* p, const double* w) {
+        ((double2*)p)[0] = make_double2(w[0], w[1]);
+        ((double2*)p)[1] = make_double2(w[2], w[3]);
     }
 };
 
@@ -251,18 +259,3 @@ k_sweep_ve(int n, int G, FastDiv divG, const int* __restrict__ eci, const M* __r
     }
 }
 
-// ELL-4 copy of a CSR matrix (see k_sweep_ve); err = 1 when a row has more
-// than 4 entries (the copy is then not used).
-template <typename M>
-__global__ void k_csr_to_ell4(int n, const int* __restrict__ rp, const int* __restrict__ ci, const M* __restrict__ v,
-                              int* __restrict__ eci, M* __restrict__ ev, int* __restrict__ err) {
-    const int i = blockIdx.x * BAMG_BLK + threadIdx.x;
-    if (i >= n) return;
-    const int p0 = rp[i], len = rp[i + 1] - p0;
-    if (len > 4) { *err = 1; return; }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        eci[(size_t)i * 4 + u] = u < len ? ci[p0 + u] : i;
-        ev[(size_t)i * 4 + u] = u < len ? v[p0 + u] : (M)0;
-    }
-}

@@ -245,6 +245,32 @@ def test_sweep_variants_give_the_same_bits(variant, monkeypatch):
     assert (st.sweep_vw, st.sweep_bs, st.sweep_rp) == (vw, bs, rp[0] if rp else 1)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_ell_copies_give_the_same_bits(precision, monkeypatch):
+    # the ELL-4 copy of B_0 (written by the pass that builds B_0 from A, with
+    # its FP64 values for the outer products in the mixed form) and the ELL-9
+    # copies of the coarse grid levels add the same terms in the same order
+    # as the CSR forms: the test vectors, the operators and the solution agree
+    # bit for bit with BAMG_SWEEP_ELL=0
+    ch = C.tandem_queue(40)
+    opts = B.default_options(levels=3, precision=B.MIXED if precision == "mixed" else B.FP64)
+    out = {}
+    for ell in ("0", "1"):
+        monkeypatch.setenv("BAMG_SWEEP_ELL", ell)
+        h = B.Hierarchy.from_chain(ch, 12, opts)
+        x = torch.empty(ch.n, dtype=torch.float64, device="cuda")
+        info = h.solve(x, 1e-12, 100)
+        assert info.converged
+        out[ell] = (h.stats().sweep_ell, x.cpu().numpy(), h.export(0, B.X_U),
+                    [h.export(l, it) for l in (0, 1, 2) for it in (B.X_B_COL, B.X_B_VAL)])
+        h.close()
+    assert (out["0"][0], out["1"][0]) == (0, 1)
+    for a, b in zip(out["0"][1:3], out["1"][1:3]):
+        assert np.array_equal(a, b)
+    for a, b in zip(out["0"][3], out["1"][3]):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("rows", ["14", "56"])
 def test_galerkin_rows_per_workgroup_give_the_same_bits(rows, monkeypatch):
     # the fused Galerkin launch shapes the autotuner chooses from (14, 28 or

@@ -74,3 +74,31 @@ def test_mixed_hierarchy_close_to_fp64():
         a, b = _csr(h32, l, "B"), _csr(h64, l, "B")
         rel = sp.linalg.norm(a - b) / sp.linalg.norm(b)
         assert rel <= 1e-3, (l, rel)
+
+
+@pytest.mark.parametrize("name,make,r,levels", CASES[:5])
+def test_mixed_coarsest_eigenpairs(name, make, r, levels):
+    # The mixed form's Arnoldi multiplies by W rounded to FP32 (vectors, sums
+    # and the Hessenberg problem stay FP64).  Entrywise rounding 2^-24 moves
+    # an eigenvalue theta of W by at most kappa * 2^-24 ||W||_F, and the
+    # wanted theta are the largest, of the order of ||W||_2 >= ||W||_F /
+    # sqrt(n): for these coarsest grids (n <= 121) that is below 1e-6 kappa
+    # relative, so lam = 1/theta within 1e-5 and eigenvectors within 1e-3
+    # allow kappa ~ 10.  An error in the product's indexing moves them by O(1).
+    ch = make()
+    h = B.Hierarchy.from_chain(ch, r, B.default_options(levels=levels, stop_after=2, precision=B.MIXED))
+    L = levels - 1
+    BL = _csr(h, L, "B").toarray()
+    TL = _csr(h, L, "T").toarray()
+    nL = BL.shape[0]
+    V = h.export(L, B.X_V).reshape(nL, -1)
+    lam = h.export(L, B.X_LAMBDA).reshape(-1, 2)
+    _, entries, Vo = O.coarsest_eigs(BL, TL, 6)
+    assert V.shape[1] == Vo.shape[1]
+    for e in entries[1:]:
+        c = e.cols[0]
+        got = complex(lam[c, 0], lam[c, 1])
+        assert abs(got - e.lam) <= 1e-5 * abs(e.lam), (nL, got, e.lam)
+        for cc in e.cols:
+            assert np.abs(V[:, cc] - Vo[:, cc]).max() <= 1e-3, (nL, cc)
+    h.close()

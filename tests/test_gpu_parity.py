@@ -268,6 +268,33 @@ def test_vcycle_matches_oracle(name, make, r, levels):
     assert np.abs(got - want).max() <= 1e-9 * np.abs(want).max()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("relax", ["jacobi", "mcgs"])
+@pytest.mark.parametrize("name,make,r,levels", [CASES[1], CASES[2], CASES[5]])
+def test_fused_cycle_passes_give_the_same_bits(name, make, r, levels, relax, precision, monkeypatch):
+    # On small coarse grid levels the cycle forms the prolongation inside the
+    # first post-smoothing sweep; BAMG_CYCLE_FUSE=0 takes the separate
+    # launches.  Both are the same sums in the same order, so the cycle's
+    # output must agree bit for bit.
+    ch = make()
+    opts = B.default_options(levels=levels, cycle_mode=1,
+                             precision=B.MIXED if precision == "mixed" else B.FP64,
+                             relax=B.RELAX_MCGS if relax == "mcgs" else B.RELAX_JACOBI)
+    h = B.Hierarchy.from_chain(ch, r, opts)
+    f0 = np.random.default_rng(5).random(ch.n)
+    f0 -= f0.mean()
+    f = torch.tensor(f0, device="cuda")
+    out = {}
+    for fuse in ("0", "1"):
+        monkeypatch.setenv("BAMG_CYCLE_FUSE", fuse)
+        e = torch.empty_like(f)
+        h.apply_vcycle(f, e)
+        out[fuse] = e.cpu().numpy()
+    h.close()
+    assert np.abs(out["1"]).max() > 0
+    assert np.array_equal(out["0"], out["1"]), np.abs(out["0"] - out["1"]).max()
+
+
 @pytest.mark.parametrize("name,make,r,levels", CASES)
 def test_stationary_matches_oracle(name, make, r, levels):
     ch = make()
