@@ -593,6 +593,7 @@ struct Engine : bamg_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_s = nullptr;     // capture needs a stream other than the legacy default one
+    bool pivot_pending = false;      // the last coarsest inverse's pivot not yet checked
     bool cycle_decided = false, use_graph = false;
     // learned form
     MlpPack* mlp_pk = nullptr;
@@ -1409,11 +1410,7 @@ struct Engine : bamg_ctx {
         hipLaunchKernelGGL(k_cz_absmax_sparse<T>, dim3(64, nch), dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, part);
         LAUNCH(k_cz_absmax_final, nch, BAMG_BLK, s, 64, (const double*)part, scale);
         HIPCHK(hipGetLastError());
-        {
-            std::vector<double> big(nch, 1e300);
-            HIPCHK(hipMemcpyAsync(minpiv, big.data(), sizeof(double) * nch, hipMemcpyHostToDevice, s));
-            sync();
-        }
+        LAUNCH(k_fill, ceil_div(nch, BAMG_BLK), BAMG_BLK, s, (long long)nch, 1e300, minpiv);
         if (dense_fallback) {
             dense_gj_inverse();
         } else {
@@ -1490,14 +1487,25 @@ struct Engine : bamg_ctx {
         // c = T^T 1, cy = c^T y
         hipLaunchKernelGGL(k_cz_colsum<T>, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, cpool);
         LAUNCH(k_cz_dot, nch, BAMG_BLK, s, (const CoarseDesc*)cd, (const double*)cpool, (const double*)ypool, cy, 1);
+        // the smallest pivot is read at the next read-back (check_pivot), so
+        // that the host can go on issuing work meanwhile
+        pivot_pending = true;
+        if (MIXED)
+            hipLaunchKernelGGL(k_cz_w_f32, dim3(std::min(2048, nblk((long long)maxnL * maxnL)), nch), dim3(BAMG_BLK), 0,
+                               s, (const CoarseDesc*)cd, (const double*)Wp, Wfp);
+    }
+
+    // The smallest pivot of the last coarsest inverse (relative to max |B_L|):
+    // BAMG_ESINGULAR below 1e-12.  Called before anything read back depends
+    // on the inverse; the kernels in between only compute with its values.
+    void check_pivot() {
+        if (!pivot_pending) return;
+        pivot_pending = false;
         std::vector<double> mp = getn(minpiv, nch);
         double mn = 1e300;
         for (double v : mp) mn = std::min(mn, v);
         st.coarsest_min_pivot = mn;
         if (!(mn > 1e-12)) fail(BAMG_ESINGULAR, "coarsest pivot %.3e below 1e-12 of max |B_L|", mn);
-        if (MIXED)
-            hipLaunchKernelGGL(k_cz_w_f32, dim3(std::min(2048, nblk((long long)maxnL * maxnL)), nch), dim3(BAMG_BLK), 0,
-                               s, (const CoarseDesc*)cd, (const double*)Wp, Wfp);
     }
 
     // The coarsest inverse of a bordered grid from the main part's inverse
@@ -1620,6 +1628,7 @@ struct Engine : bamg_ctx {
         hipLaunchKernelGGL(k_cz_hess_vec, dim3(HSEL_THETA / 2, nch), dim3(BAMG_WAVE), 0, s, (const CoarseDesc*)cd,
                            (const double*)Hh, HS, (const int*)nsel, NS, (const double*)sel_lam, LSS, sel_s, SS);
         HIPCHK(hipGetLastError());
+        check_pivot();
         std::vector<int> hs = getn(nsel, (size_t)nch * NS);
         int emax = 0;
         for (int c = 0; c < nch; ++c) {
@@ -2077,6 +2086,7 @@ struct Engine : bamg_ctx {
 
     void finish_setup(std::chrono::steady_clock::time_point t0) {
         sync();
+        check_pivot();
         st.t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         st.n_levels = (int)L.size();
         st.n_v = nvmax;
