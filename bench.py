@@ -254,6 +254,7 @@ def _kernel_detail(stats):
         "lsfit_first_pass": _per_launch(stats, "lsfit_ms", "lsfit_launches", "lsfit_bytes"),
         "lsfit_recompute_pass": _per_launch(stats, "lsfit2_ms", "lsfit2_launches", "lsfit2_bytes"),
         "coarsest_min_pivot": stats[-1].coarsest_min_pivot,
+        "coarsest_arnoldi_steps": stats[-1].arnoldi_steps,
         "cycle_graph": stats[-1].cycle_graph,
         "sweep_tune_ms_total": round(stats[-1].tune_ms, 2),
     }

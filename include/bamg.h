@@ -219,6 +219,12 @@ typedef struct {
     int64_t gal_csr_bytes, lsfit2_bytes;
     int32_t sweep_rp;       /* row pieces per thread of the level-0 sweep (1, or
                                2 on the ELL-4 copy; autotuned with sweep_vw)  */
+    int32_t arnoldi_steps;  /* Arnoldi steps of the last coarsest eigensolve:
+                               min(40, n_L - 1), or 32 when every wanted Ritz
+                               pair's relative residual |h_{m+1,m} s_m| / |theta|
+                               is at most 1e-9 after 32 steps (checked once;
+                               BAMG_ARNOLDI_CHECK=0 in the environment turns
+                               the check off)                                   */
 } bamg_stats;
 
 typedef struct {

@@ -80,7 +80,7 @@ class Stats(C.Structure):
                 ("dense_update_launches", C.c_int32), ("dense_update_flops", C.c_double),
                 ("sweep_ell", C.c_int32), ("gal_csr_ms", C.c_double), ("lsfit2_ms", C.c_double),
                 ("gal_csr_launches", C.c_int32), ("lsfit2_launches", C.c_int32), ("gal_csr_bytes", C.c_int64),
-                ("lsfit2_bytes", C.c_int64), ("sweep_rp", C.c_int32)]
+                ("lsfit2_bytes", C.c_int64), ("sweep_rp", C.c_int32), ("arnoldi_steps", C.c_int32)]
 
 
 class MlpTrainOpts(C.Structure):

@@ -74,6 +74,11 @@ inline int nblk(long long n) { return (int)std::max<long long>(1, (n + BAMG_BLK 
 // a large chain fills the chip and a chain's summation order does not depend
 // on the other chains of its batch.
 constexpr int SEG_ROWS = 1024;
+// The coarsest Arnoldi process stops after ARN_CHECK steps when every wanted
+// Ritz pair's relative residual is at most ARN_TOL already (checked once;
+// otherwise it runs all its steps).
+constexpr int ARN_CHECK = 32;
+constexpr double ARN_TOL = 1e-9;
 // Coarse grid levels of at most this many rows take the prolongation and the
 // first post-smoothing sweep of the cycle in one pass (measured on the C2
 // hierarchy: 5.5-5.8 us against 8.0-8.3 us for the two launches at 16K and
@@ -594,6 +599,7 @@ struct Engine : bamg_ctx {
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_s = nullptr;     // capture needs a stream other than the legacy default one
     bool pivot_pending = false;      // the last coarsest inverse's pivot not yet checked
+    int arn_used = 1 << 30;          // Arnoldi steps the last coarsest eigenpairs came from (cap)
     bool cycle_decided = false, use_graph = false;
     // learned form
     MlpPack* mlp_pk = nullptr;
@@ -1235,6 +1241,13 @@ struct Engine : bamg_ctx {
         HIPCHK(hipGetLastError());
     }
 
+    // BAMG_ARNOLDI_CHECK=0 in the environment: the coarsest Arnoldi process
+    // always runs all its steps (no convergence check after ARN_CHECK).
+    static bool arnoldi_check_on() {
+        const char* e = getenv("BAMG_ARNOLDI_CHECK");
+        return !(e && e[0] == '0');
+    }
+
     // BAMG_CYCLE_FUSE=0 in the environment: the cycle takes the
     // prolongation and the first post-smoothing sweep of a small coarse grid
     // level as separate launches (the fused pass computes the same bits).
@@ -1603,15 +1616,9 @@ struct Engine : bamg_ctx {
         const int want = o.n_eig - 1;
         const dim3 gv(nblk(maxnL), nch);
         const dim3 gw(ceil_div(maxnL, 4), nch);
-        if (want > 0 && AMmax >= 1) {
-            zero(Hh, sizeof(double) * nch * HS);
-            hipLaunchKernelGGL(k_cz_arn_start, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, o.seed, Vb);
-            HIPCHK(hipGetLastError());
-            // the start vector is basis column 0 (no H entry), then t1 = T v_0
-            arnoldi_start();
-            hipLaunchKernelGGL(k_cz_tv<T>, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, 0, (const double*)Vb, t1);
-            const dim3 gw2(ceil_div(maxnL, 2), nch);
-            for (int j = 0; j < AMmax; ++j) {
+        const dim3 gw2(ceil_div(maxnL, 2), nch);
+        auto steps = [&](int j0, int j1) {
+            for (int j = j0; j < j1; ++j) {
                 // the mixed form multiplies by its FP32 copy of W (half the bytes)
                 if (MIXED)
                     hipLaunchKernelGGL(k_cz_arn_gemv_f32, gw2, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, j,
@@ -1622,12 +1629,50 @@ struct Engine : bamg_ctx {
                 HIPCHK(hipGetLastError());
                 arnoldi_orthogonalize(j);
             }
+        };
+        auto eig = [&](int mcap) {
+            LAUNCH(k_cz_hess, nch, BAMG_WAVE, s, (const CoarseDesc*)cd, want, mcap, (const double*)Hh, HS, nsel, NS,
+                   sel_lam, LSS);
+            hipLaunchKernelGGL(k_cz_hess_vec, dim3(HSEL_THETA / 2, nch), dim3(BAMG_WAVE), 0, s, (const CoarseDesc*)cd,
+                               mcap, (const double*)Hh, HS, (const int*)nsel, NS, (const double*)sel_lam, LSS, sel_s,
+                               SS);
+            HIPCHK(hipGetLastError());
+        };
+        // Arnoldi steps used: every chain's am, or ARN_CHECK when the Ritz
+        // pairs of the first ARN_CHECK steps already meet ARN_TOL for every
+        // chain that runs more
+        arn_used = 1 << 30;
+        if (want > 0 && AMmax >= 1) {
+            zero(Hh, sizeof(double) * nch * HS);
+            hipLaunchKernelGGL(k_cz_arn_start, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, o.seed, Vb);
+            HIPCHK(hipGetLastError());
+            // the start vector is basis column 0 (no H entry), then t1 = T v_0
+            arnoldi_start();
+            hipLaunchKernelGGL(k_cz_tv<T>, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, 0, (const double*)Vb, t1);
+            if (AMmax > ARN_CHECK && arnoldi_check_on()) {
+                steps(0, ARN_CHECK);
+                eig(ARN_CHECK);
+                LAUNCH(k_cz_ritz_check, ceil_div(nch, 64), 64, s, nch, (const CoarseDesc*)cd, ARN_CHECK,
+                       (const double*)Hh, HS, (const int*)nsel, NS, (const double*)sel_lam, LSS, (const double*)sel_s,
+                       SS, ARN_TOL, itmp);
+                check_pivot();
+                std::vector<int> okv = getn(itmp, nch);
+                bool all = true;
+                for (int v : okv) all &= v != 0;
+                if (all) {
+                    arn_used = ARN_CHECK;
+                } else {
+                    steps(ARN_CHECK, AMmax);
+                    eig(1 << 30);
+                }
+            } else {
+                steps(0, AMmax);
+                eig(1 << 30);
+            }
+        } else {
+            eig(1 << 30);
         }
-        LAUNCH(k_cz_hess, nch, BAMG_WAVE, s, (const CoarseDesc*)cd, want, (const double*)Hh, HS, nsel, NS, sel_lam,
-               LSS);
-        hipLaunchKernelGGL(k_cz_hess_vec, dim3(HSEL_THETA / 2, nch), dim3(BAMG_WAVE), 0, s, (const CoarseDesc*)cd,
-                           (const double*)Hh, HS, (const int*)nsel, NS, (const double*)sel_lam, LSS, sel_s, SS);
-        HIPCHK(hipGetLastError());
+        st.arnoldi_steps = std::min(AMmax, arn_used);
         check_pivot();
         std::vector<int> hs = getn(nsel, (size_t)nch * NS);
         int emax = 0;
@@ -1651,7 +1696,8 @@ struct Engine : bamg_ctx {
             hipLaunchKernelGGL(k_cz_ycol<T>, gvl, dim3(BAMG_BLK), 0, s, cdl, (const double*)ypool,
                                (const double*)(cy + c0), lv.V, VS);
             for (int e = 0; e < emax; ++e) {
-                hipLaunchKernelGGL(k_cz_ritz, gvl, dim3(BAMG_BLK), 0, s, cdl, e, (const int*)(nsel + (size_t)c0 * NS), NS,
+                hipLaunchKernelGGL(k_cz_ritz, gvl, dim3(BAMG_BLK), 0, s, cdl, e, arn_used,
+                                   (const int*)(nsel + (size_t)c0 * NS), NS,
                                    (const double*)Vb, (const double*)(sel_s + (size_t)c0 * SS), SS, rre, rim);
                 hipLaunchKernelGGL(k_cz_eigvec<T>, dim3(c1 - c0), dim3(BAMG_BLK), 0, s, cdl, e,
                                    (const int*)(nsel + (size_t)c0 * NS), NS, (const double*)(sel_lam + (size_t)c0 * LSS),

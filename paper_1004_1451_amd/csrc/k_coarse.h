@@ -1803,16 +1803,18 @@ __global__ void k_cz_arn_normalize(const CoarseDesc* __restrict__ cd, int j, dou
         u[i] = nrm > 0 ? u[i] / nrm : 0.0;
 }
 
-// Ritz vector of entry e of chain (blockIdx.y): v = Vb[:, 0:am] s_e.
-__global__ void k_cz_ritz(const CoarseDesc* __restrict__ cd, int e, const int* __restrict__ nsel, int NS,
+// Ritz vector of entry e of chain (blockIdx.y): v = Vb[:, 0:m] s_e, m =
+// min(am, mcap) Arnoldi steps.
+__global__ void k_cz_ritz(const CoarseDesc* __restrict__ cd, int e, int mcap, const int* __restrict__ nsel, int NS,
                           const double* __restrict__ Vb, const double* __restrict__ sel_s, int SS,
                           double* __restrict__ rre, double* __restrict__ rim) {
     const CoarseDesc d = cd[blockIdx.y];
     if (e >= nsel[(size_t)blockIdx.y * NS]) return;
     const double* s = sel_s + (size_t)blockIdx.y * SS + (size_t)e * 2 * d.am;
+    const int m = min(d.am, mcap);
     for (int i = blockIdx.x * BAMG_BLK + threadIdx.x; i < d.n; i += gridDim.x * BAMG_BLK) {
         double a = 0, b = 0;
-        for (int j = 0; j < d.am; ++j) {
+        for (int j = 0; j < m; ++j) {
             double v = Vb[d.aoff + (size_t)j * d.n + i];
             a += v * s[2 * j]; b += v * s[2 * j + 1];
         }
@@ -1923,11 +1925,11 @@ k_hess_near0(int k, const int* __restrict__ act, const double* __restrict__ Hall
     hessenberg_near_zero_body(k, Hall + (size_t)c * HS, ld, eta + (size_t)c * ES, fail + c);
 }
 
-// One wavefront per chain: eigenvalues of its Arnoldi Hessenberg matrix
-// (stride HS), selection and eigenvectors (see hessenberg_eig_body).
-// Chains without eigenpairs report no selection.
+// One wavefront per chain: eigenvalues of the leading min(am, mcap) steps of
+// its Arnoldi Hessenberg matrix (stride HS), selection and eigenvectors (see
+// hessenberg_select_body).  Chains without eigenpairs report no selection.
 __global__ void __launch_bounds__(BAMG_WAVE)
-k_cz_hess(const CoarseDesc* __restrict__ cd, int want, const double* __restrict__ Hh, int HS,
+k_cz_hess(const CoarseDesc* __restrict__ cd, int want, int mcap, const double* __restrict__ Hh, int HS,
           int* __restrict__ nsel, int NS, double* __restrict__ sel_lam, int LS) {
     const int c = blockIdx.x;
     const CoarseDesc d = cd[c];
@@ -1935,17 +1937,46 @@ k_cz_hess(const CoarseDesc* __restrict__ cd, int want, const double* __restrict_
         if (threadIdx.x == 0) { nsel[(size_t)c * NS] = 0; nsel[(size_t)c * NS + 1] = 0; nsel[(size_t)c * NS + 2] = 0; }
         return;
     }
-    hessenberg_select_body(d.am, want, Hh + (size_t)c * HS, nsel + (size_t)c * NS, sel_lam + (size_t)c * LS);
+    hessenberg_select_body(min(d.am, mcap), d.am + 1, want, Hh + (size_t)c * HS, nsel + (size_t)c * NS,
+                           sel_lam + (size_t)c * LS);
 }
 
 // The eigenvectors of the selected eigenvalues, one wavefront per entry e
 // (blockIdx.x) and chain (blockIdx.y), all at once.
 __global__ void __launch_bounds__(BAMG_WAVE)
-k_cz_hess_vec(const CoarseDesc* __restrict__ cd, const double* __restrict__ Hh, int HS, const int* __restrict__ nsel,
-              int NS, const double* __restrict__ sel_lam, int LS, double* __restrict__ sel_s, int SS) {
+k_cz_hess_vec(const CoarseDesc* __restrict__ cd, int mcap, const double* __restrict__ Hh, int HS,
+              const int* __restrict__ nsel, int NS, const double* __restrict__ sel_lam, int LS,
+              double* __restrict__ sel_s, int SS) {
     const int c = blockIdx.y, e = blockIdx.x;
     const CoarseDesc d = cd[c];
     if (d.am < 1 || e >= nsel[(size_t)c * NS] || nsel[(size_t)c * NS + 2]) return;
     const double* th = sel_lam + (size_t)c * LS + HSEL_THETA + 2 * e;
-    hessenberg_vec_body(d.am, Hh + (size_t)c * HS, th[0], th[1], sel_s + (size_t)c * SS + (size_t)e * 2 * d.am);
+    hessenberg_vec_body(min(d.am, mcap), d.am + 1, Hh + (size_t)c * HS, th[0], th[1],
+                        sel_s + (size_t)c * SS + (size_t)e * 2 * d.am);
+}
+
+// Whether the Ritz pairs selected from the first m = min(am, mcap) Arnoldi
+// steps are converged (one thread per chain): the residual of a Ritz pair
+// (theta, V_m s) with ||s||_2 = 1 is |h_{m+1,m}| |s_m| (the Arnoldi
+// relation), taken relative to |theta|; ok[c] = 1 when every selected
+// entry's is at most tol, or when the chain ran all its steps (m = am).
+__global__ void k_cz_ritz_check(int nch, const CoarseDesc* __restrict__ cd, int mcap, const double* __restrict__ Hh,
+                                int HS, const int* __restrict__ nsel, int NS, const double* __restrict__ sel_lam,
+                                int LS, const double* __restrict__ sel_s, int SS, double tol, int* __restrict__ ok) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nch) return;
+    const CoarseDesc d = cd[c];
+    const int m = min(d.am, mcap);
+    if (d.am < 1 || m >= d.am) { ok[c] = 1; return; }
+    const int* ns = nsel + (size_t)c * NS;
+    if (ns[2]) { ok[c] = 0; return; }
+    const double h = fabs(Hh[(size_t)c * HS + (size_t)(m - 1) * (d.am + 1) + m]);
+    int good = 1;
+    for (int e = 0; e < ns[0]; ++e) {
+        const double* th = sel_lam + (size_t)c * LS + HSEL_THETA + 2 * e;
+        const double* sv = sel_s + (size_t)c * SS + (size_t)e * 2 * d.am + 2 * (m - 1);
+        const double res = h * sqrt(sv[0] * sv[0] + sv[1] * sv[1]);
+        if (!(res <= tol * sqrt(th[0] * th[0] + th[1] * th[1]))) good = 0;
+    }
+    ok[c] = good;
 }

@@ -738,8 +738,9 @@ __device__ void hess_shift_apply_wave(int m, const double* U, const double* fm, 
     lds_sync();
 }
 
-// One wavefront: eigenvalues theta of H_m (Hessenberg, column-major (m+1) x m
-// in Hh) and the selection of the `want` nonzero lam = 1/theta of smallest
+// One wavefront: eigenvalues theta of H_m (the leading m x m block of the
+// Hessenberg matrix stored column-major with leading dimension ld in Hh) and
+// the selection of the `want` nonzero lam = 1/theta of smallest
 // |lam| (largest |theta|; a conjugate pair counts as two and is never split,
 // so one more at a split; among equal moduli the member with Im(lam) > 0
 // first).  Outputs:
@@ -748,8 +749,8 @@ __device__ void hess_shift_apply_wave(int m, const double* U, const double* fm, 
 //   sel_lam[HSEL_THETA + 2e..] = its theta (the member with Im <= 0), from
 //   which hessenberg_vec_body finds the eigenvector.
 #define HSEL_THETA 16
-__device__ void hessenberg_select_body(int m, int want, const double* __restrict__ Hh, int* __restrict__ nsel_out,
-                                       double* __restrict__ sel_lam) {
+__device__ void hessenberg_select_body(int m, int ld, int want, const double* __restrict__ Hh,
+                                       int* __restrict__ nsel_out, double* __restrict__ sel_lam) {
     __shared__ double A[HQR_MAXM * HQR_LD];
     __shared__ double wr[HQR_MAXM], wi[HQR_MAXM];
     __shared__ int used[HQR_MAXM];
@@ -757,7 +758,7 @@ __device__ void hessenberg_select_body(int m, int want, const double* __restrict
     const int lane = threadIdx.x;
     if (lane == 0) fail = 0;
     for (int i = 0; i < m; ++i)
-        if (lane < m) A[i * HQR_LD + lane] = (i <= lane + 1) ? Hh[(size_t)lane * (m + 1) + i] : 0.0;
+        if (lane < m) A[i * HQR_LD + lane] = (i <= lane + 1) ? Hh[(size_t)lane * ld + i] : 0.0;
     if (lane < HQR_MAXM) used[lane] = 0;
     __threadfence_block();
     lds_sync();
@@ -801,13 +802,14 @@ __device__ void hessenberg_select_body(int m, int want, const double* __restrict
     if (lane == 0) { nsel_out[0] = ne; nsel_out[1] = ncols; nsel_out[2] = fail; }
 }
 
-// One wavefront: the eigenvector of H_m (column-major (m+1) x m in Hh) for
-// the eigenvalue theta = (thr, thi), by three steps of inverse iteration
+// One wavefront: the eigenvector of H_m (the leading m x m block, column-major
+// with leading dimension ld in Hh) for the eigenvalue theta = (thr, thi), by
+// three steps of inverse iteration
 // with H - theta I from the start vector of ones, each normalised to
 // ||z||_2 = 1; (re, im) pairs into out[2j..2j+1] (im = 0 for a real theta).
 // A row-major copy of H_m stays in LDS for the elimination, which reads one
 // row per step.
-__device__ void hessenberg_vec_body(int m, const double* __restrict__ Hh, double thr, double thi,
+__device__ void hessenberg_vec_body(int m, int ld, const double* __restrict__ Hh, double thr, double thi,
                                     double* __restrict__ out) {
     __shared__ double U[HQR_MAXM * HQR_LD];
     __shared__ double Hs[HQR_MAXM * HQR_MAXM];
@@ -817,7 +819,7 @@ __device__ void hessenberg_vec_body(int m, const double* __restrict__ Hh, double
     double hn = 0;
     for (int i = 0; i < m; ++i) {
         double v = 0;
-        if (lane < m) v = (i <= lane + 1) ? Hh[(size_t)lane * (m + 1) + i] : 0.0;
+        if (lane < m) v = (i <= lane + 1) ? Hh[(size_t)lane * ld + i] : 0.0;
         if (lane < m) Hs[i * m + lane] = v;
         hn = fmax(hn, fabs(v));
     }

@@ -170,6 +170,36 @@ def test_coarsest_matches_oracle(name, make, r, levels):
             assert np.abs(V[:, cc] - Vo[:, cc]).max() <= 1e-5, cc
 
 
+def test_arnoldi_convergence_check_at_32_steps(monkeypatch):
+    # A 65 x 65 coarsest level (tandem 128^2, two levels) runs 40 Arnoldi
+    # steps unless the wanted Ritz pairs of the first 32 already have
+    # relative residuals |h_{33,32} s_32| / |theta| <= 1e-9.  Both ways the
+    # eigenpairs meet the oracle's bar (lam 1e-7, vectors 1e-5), and the two
+    # agree with each other to the residual bound.
+    ch = C.tandem_queue(127)
+    out = {}
+    for chk in ("0", "1"):
+        monkeypatch.setenv("BAMG_ARNOLDI_CHECK", chk)
+        h = B.Hierarchy.from_chain(ch, 8, B.default_options(levels=2, stop_after=2))
+        BL = _csr(h, 1, "B").toarray()
+        TL = _csr(h, 1, "T").toarray()
+        nL = BL.shape[0]
+        assert nL == 65 * 65
+        out[chk] = (h.stats().arnoldi_steps, h.export(1, B.X_LAMBDA).reshape(-1, 2),
+                    h.export(1, B.X_V).reshape(nL, -1))
+        h.close()
+    assert out["0"][0] == 40 and out["1"][0] in (32, 40)
+    _, entries, Vo = O.coarsest_eigs(BL, TL, 6)
+    for chk in ("0", "1"):
+        lam, V = out[chk][1], out[chk][2]
+        for e in entries[1:]:
+            c = e.cols[0]
+            assert abs(complex(lam[c, 0], lam[c, 1]) - e.lam) <= 1e-7 * abs(e.lam), (chk, c)
+            for cc in e.cols:
+                assert np.abs(V[:, cc] - Vo[:, cc]).max() <= 1e-5, (chk, cc)
+    print("arnoldi steps with the check:", out["1"][0], flush=True)
+
+
 # Coarsest grids with few block rows: the two-sided block factorisation of
 # grids without the periodic arrow meets in block row m = (K + 1) / 2 of the
 # K + 1 rows, so one and two rows (no top or no bottom part), three rows and
