@@ -2482,8 +2482,10 @@ struct Engine : bamg_ctx {
                 const int P0 = L[0].segp;
                 const dim3 gsg(P0, nch);
                 gs_dispatch(j, [&](auto kc) {
-                    hipLaunchKernelGGL(k_gs_dots<decltype(kc)::value>, gsg, dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, vld, j,
-                                       (const int*)act, (const double*)Vk, (const double*)wk, part, GS);
+                    hipLaunchKernelGGL((k_gs_dots<decltype(kc)::value, false>), gsg, dim3(BAMG_BLK), 0, s, g0, SEG_ROWS,
+                                       vld, j, (const int*)act, (const double*)Vk, (const double*)wk, part, GS,
+                                       (const int*)nullptr, (const double*)nullptr, (const double*)nullptr, 1.0,
+                                       (double*)nullptr);
                 });
                 hipLaunchKernelGGL(k_gs_final, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0,
                                    (const int*)act, (const double*)part, GS, hbuf, GS);
@@ -2628,16 +2630,27 @@ struct Engine : bamg_ctx {
                     }
                     precondition(vj, zj);
                     ++inf.cycles;
-                    outer_spmv((const double*)zj, 1.0, wk, RowMask{g0, nch, cmask});
-                    // Gram-Schmidt with the delayed second pass: dots of w, the
-                    // per-chain step (finish v_j, correct column j-1, column j,
-                    // Givens), and, for chains that go on, the update pass that
-                    // finishes q_j and makes v_{j+1} with its dots
+                    // w = B z_j, then Gram-Schmidt with the delayed second
+                    // pass: dots of w, the per-chain step (finish v_j, correct
+                    // column j-1, column j, Givens), and, for chains that go
+                    // on, the update pass that finishes q_j and makes v_{j+1}
+                    // with its dots.  With the ELL-4 copy of B_0 the product
+                    // is formed inside the dots pass.
                     const int P0 = L[0].segp;
                     const dim3 gsg(P0, nch);
+                    if (!b0ev) outer_spmv((const double*)zj, 1.0, wk, RowMask{g0, nch, cmask});
                     gs_dispatch(j, [&](auto kc) {
-                        hipLaunchKernelGGL(k_gs_dots<decltype(kc)::value>, gsg, dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, vld,
-                                           j, (const int*)act, (const double*)Vk, (const double*)wk, part, GS);
+                        constexpr int K = decltype(kc)::value;
+                        if (b0ev)
+                            hipLaunchKernelGGL((k_gs_dots<K, true>), gsg, dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, vld, j,
+                                               (const int*)act, (const double*)Vk, (const double*)nullptr, part, GS,
+                                               (const int*)L[0].B.eci, (const double*)b0ev, (const double*)zj, 1.0,
+                                               wk);
+                        else
+                            hipLaunchKernelGGL((k_gs_dots<K, false>), gsg, dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, vld,
+                                               j, (const int*)act, (const double*)Vk, (const double*)wk, part, GS,
+                                               (const int*)nullptr, (const double*)nullptr, (const double*)nullptr,
+                                               1.0, (double*)nullptr);
                     });
                     hipLaunchKernelGGL(k_gs_final, dim3(j + 2, nch), dim3(BAMG_BLK), 0, s, g0, SEG_ROWS, P0,
                                        (const int*)act, (const double*)part, GS, hbuf, GS);

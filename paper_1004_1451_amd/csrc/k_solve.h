@@ -286,10 +286,17 @@ __global__ void k_seg_reduce_final(const ChainGeo* __restrict__ geo, int seg_row
 template <int K>
 struct GsRows { static constexpr int U = K <= 2 ? 4 : K <= 4 ? 2 : 1; };
 
-template <int K>
+//
+// SPMV: w is not read but formed here as w = alpha B z from the ELL-4 copy of
+// B_0 (eci, ev; the sums of k_spmv_e in its order, so the same bits) and
+// stored to wout for the update pass: the outer product and the dots pass in
+// one launch.
+template <int K, bool SPMV = false>
 __global__ void __launch_bounds__(BAMG_BLK)
 k_gs_dots(const ChainGeo* __restrict__ geo, int seg_rows, int ldv, int nb, const int* __restrict__ act,
-          const double* __restrict__ V, const double* __restrict__ w, double* __restrict__ part, int NDM) {
+          const double* __restrict__ V, const double* __restrict__ w, double* __restrict__ part, int NDM,
+          const int* __restrict__ eci, const double* __restrict__ ev, const double* __restrict__ z, double alpha,
+          double* __restrict__ wout) {
     __shared__ double red[(BAMG_BLK / BAMG_WAVE) * (GsRed<K>::KR + 2)];
     constexpr int U = GsRows<K>::U;
     const ChainGeo g = geo[blockIdx.y];
@@ -306,7 +313,20 @@ k_gs_dots(const ChainGeo* __restrict__ geo, int seg_rows, int ldv, int nb, const
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int r = i + u * BAMG_BLK < i1 ? i + u * BAMG_BLK : i;
-            x[u] = w[r];
+            if constexpr (SPMV) {
+                const int4 c4 = *(const int4*)(eci + (size_t)r * 4);
+                const double2 wa = ((const double2*)(ev + (size_t)r * 4))[0];
+                const double2 wb = ((const double2*)(ev + (size_t)r * 4))[1];
+                const double z0 = z[c4.x], z1 = z[c4.y], z2 = z[c4.z], z3 = z[c4.w];
+                double acc = 0;
+                acc += wa.x * z0;
+                acc += wa.y * z1;
+                acc += wb.x * z2;
+                acc += wb.y * z3;
+                x[u] = alpha * acc;
+            } else {
+                x[u] = w[r];
+            }
 #pragma unroll
             for (int b = 0; b < K; ++b) q[u][b] = (b < nb ? V + (size_t)b * ldv : y)[r];
             yi[u] = y[r];
@@ -315,6 +335,7 @@ k_gs_dots(const ChainGeo* __restrict__ geo, int seg_rows, int ldv, int nb, const
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (i + u * BAMG_BLK >= i1) break;
+            if constexpr (SPMV) wout[i + u * BAMG_BLK] = x[u];
 #pragma unroll
             for (int b = 0; b < K; ++b) acc[b] += q[u][b] * x[u];
             ey += yi[u] * x[u];
