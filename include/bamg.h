@@ -220,11 +220,12 @@ typedef struct {
     int32_t sweep_rp;       /* row pieces per thread of the level-0 sweep (1, or
                                2 on the ELL-4 copy; autotuned with sweep_vw)  */
     int32_t arnoldi_steps;  /* Arnoldi steps of the last coarsest eigensolve:
-                               min(40, n_L - 1), or 32 when every wanted Ritz
-                               pair's relative residual |h_{m+1,m} s_m| / |theta|
-                               is at most 1e-9 after 32 steps (checked once;
+                               min(40, n_L - 1), or m = 20 or 30 when every
+                               wanted Ritz pair's relative residual
+                               |h_{m+1,m} s_m| / |theta| is at most 1e-9 after
+                               m steps (checked at 20, then 30;
                                BAMG_ARNOLDI_CHECK=0 in the environment turns
-                               the check off)                                   */
+                               the checks off)                                  */
 } bamg_stats;
 
 typedef struct {

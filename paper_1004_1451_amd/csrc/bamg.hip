@@ -74,10 +74,10 @@ inline int nblk(long long n) { return (int)std::max<long long>(1, (n + BAMG_BLK 
 // a large chain fills the chip and a chain's summation order does not depend
 // on the other chains of its batch.
 constexpr int SEG_ROWS = 1024;
-// The coarsest Arnoldi process stops after ARN_CHECK steps when every wanted
-// Ritz pair's relative residual is at most ARN_TOL already (checked once;
-// otherwise it runs all its steps).
-constexpr int ARN_CHECK = 32;
+// The coarsest Arnoldi process stops after ARN_CHECK1 or ARN_CHECK2 steps
+// when every wanted Ritz pair's relative residual is at most ARN_TOL there
+// (otherwise it runs all its steps).
+constexpr int ARN_CHECK1 = 20, ARN_CHECK2 = 30;
 constexpr double ARN_TOL = 1e-9;
 // Coarse grid levels of at most this many rows take the prolongation and the
 // first post-smoothing sweep of the cycle in one pass (measured on the C2
@@ -1638,9 +1638,9 @@ struct Engine : bamg_ctx {
                                SS);
             HIPCHK(hipGetLastError());
         };
-        // Arnoldi steps used: every chain's am, or ARN_CHECK when the Ritz
-        // pairs of the first ARN_CHECK steps already meet ARN_TOL for every
-        // chain that runs more
+        // Arnoldi steps used: every chain's am, or a check point k (ARN_CHECK1,
+        // ARN_CHECK2) when the Ritz pairs of the first k steps already meet
+        // ARN_TOL for every chain that runs more
         arn_used = 1 << 30;
         if (want > 0 && AMmax >= 1) {
             zero(Hh, sizeof(double) * nch * HS);
@@ -1649,24 +1649,25 @@ struct Engine : bamg_ctx {
             // the start vector is basis column 0 (no H entry), then t1 = T v_0
             arnoldi_start();
             hipLaunchKernelGGL(k_cz_tv<T>, gv, dim3(BAMG_BLK), 0, s, (const CoarseDesc*)cd, 0, (const double*)Vb, t1);
-            if (AMmax > ARN_CHECK && arnoldi_check_on()) {
-                steps(0, ARN_CHECK);
-                eig(ARN_CHECK);
-                LAUNCH(k_cz_ritz_check, ceil_div(nch, 64), 64, s, nch, (const CoarseDesc*)cd, ARN_CHECK,
-                       (const double*)Hh, HS, (const int*)nsel, NS, (const double*)sel_lam, LSS, (const double*)sel_s,
-                       SS, ARN_TOL, itmp);
-                check_pivot();
-                std::vector<int> okv = getn(itmp, nch);
-                bool all = true;
-                for (int v : okv) all &= v != 0;
-                if (all) {
-                    arn_used = ARN_CHECK;
-                } else {
-                    steps(ARN_CHECK, AMmax);
-                    eig(1 << 30);
+            int done = 0;
+            if (arnoldi_check_on()) {
+                for (int k : {ARN_CHECK1, ARN_CHECK2}) {
+                    if (k >= AMmax) break;
+                    steps(done, k);
+                    done = k;
+                    eig(k);
+                    LAUNCH(k_cz_ritz_check, ceil_div(nch, 64), 64, s, nch, (const CoarseDesc*)cd, k,
+                           (const double*)Hh, HS, (const int*)nsel, NS, (const double*)sel_lam, LSS,
+                           (const double*)sel_s, SS, ARN_TOL, itmp);
+                    check_pivot();
+                    std::vector<int> okv = getn(itmp, nch);
+                    bool all = true;
+                    for (int v : okv) all &= v != 0;
+                    if (all) { arn_used = k; break; }
                 }
-            } else {
-                steps(0, AMmax);
+            }
+            if (arn_used > AMmax) {
+                steps(done, AMmax);
                 eig(1 << 30);
             }
         } else {

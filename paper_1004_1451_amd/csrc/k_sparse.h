@@ -1703,12 +1703,19 @@ __device__ __forceinline__ void eig_relax_row(int i, int ch, const ChainGeo* __r
             const double b1 = k == 2 ? bs[c] : (c + 1 < VP ? bs[c + 1] : 0.0);
             const double t0 = k == 2 ? (c > 0 ? ts[c - 1] : 0.0) : ts[c];
             const double t1 = k == 2 ? ts[c] : (c + 1 < VP ? ts[c + 1] : 0.0);
-            // r = (B - lam T) x, D = bd - lam td, correction r / D
-            const double rr = (b0 - lr * t0) + li * t1;
-            const double ri = (b1 - lr * t1) - li * t0;
-            const double dr = bd - lr * td, di = -li * td;
-            const double den = dr * dr + di * di;
-            const double q = k == 1 ? (rr * dr + ri * di) / den : (ri * dr - rr * di) / den;
+            // r = (B - lam T) x, D = bd - lam td, correction r / D; the
+            // fused multiply-adds are written out and no other contraction is
+            // allowed, so that every instantiation (every storage form of B
+            // and T) rounds the same way
+            double q;
+            {
+#pragma clang fp contract(off)
+                const double rr = fma(li, t1, fma(-lr, t0, b0));
+                const double ri = fma(-li, t0, fma(-lr, t1, b1));
+                const double dr = fma(-lr, td, bd), di = -li * td;
+                const double den = fma(dr, dr, di * di);
+                q = k == 1 ? fma(rr, dr, ri * di) / den : fma(ri, dr, -(rr * di)) / den;
+            }
             out[c] = (T)((double)xo[c] - omega * q);
         }
     }
@@ -1785,9 +1792,13 @@ k_rayleigh_partial(const ChainGeo* __restrict__ geo, int R, int KV, const int* _
             } else {
                 tr = xr; ti = xi;
             }
-            // conj(x) * y = (xr - i xi)(yr + i yi)
-            s0 += xr * br + xi * bi; s1 += xr * bi - xi * br;
-            s2 += xr * tr + xi * ti; s3 += xr * ti - xi * tr;
+            // conj(x) * y = (xr - i xi)(yr + i yi), the fused multiply-adds
+            // written out (the same roundings in every instantiation)
+            {
+#pragma clang fp contract(off)
+                s0 += fma(xr, br, xi * bi); s1 += fma(xr, bi, -(xi * br));
+                s2 += fma(xr, tr, xi * ti); s3 += fma(xr, ti, -(xi * tr));
+            }
         }
     }
     sh[0][t] = s0; sh[1][t] = s1; sh[2][t] = s2; sh[3][t] = s3;
