@@ -68,8 +68,11 @@ extern "C" {
 #define BAMG_ESINGULAR (-8)     /* coarsest pivot below 1e-12 of its column     */
 
 #define BAMG_FP64 0             /* every step in FP64                            */
-#define BAMG_MIXED 1            /* FP32 relaxation, Galerkin products and V-cycle;
-                                   FP64 norms, coarsest solve and outer iteration */
+#define BAMG_MIXED 1            /* FP32 relaxation, Galerkin products and V-cycle
+                                   (its coarsest product by an FP32 copy of B_L^+),
+                                   and the coarsest Arnoldi products by that copy;
+                                   FP64 norms, the coarsest inverse and
+                                   eigenproblem, and the outer iteration          */
 
 #define BAMG_RELAX_JACOBI 0     /* omega-Jacobi: x <- x + omega D^-1 (f - B x)    */
 #define BAMG_RELAX_MCGS 1       /* multicolour Gauss-Seidel (Section 3 names
