@@ -80,9 +80,10 @@ constexpr int SEG_ROWS = 1024;
 constexpr int ARN_CHECK1 = 20, ARN_CHECK2 = 30;
 constexpr double ARN_TOL = 1e-9;
 // Coarse grid levels of at most this many rows take the prolongation and the
-// first post-smoothing sweep of the cycle in one pass (measured on the C2
-// hierarchy: 5.5-5.8 us against 8.0-8.3 us for the two launches at 16K and
-// 66K rows, but 11.7 against 8.6 us at 263K rows).
+// first post-smoothing sweep of the cycle in one pass (measured on the
+// hierarchy of the 2048 x 2048 tandem queue: 5.5-5.8 us against 8.0-8.3 us
+// for the two launches at 16K and 66K rows, but 11.7 against 8.6 us at 263K
+// rows).
 constexpr int FUSE_ROWS = 1 << 17;
 // The TV-weight and Rayleigh partials do a sparse product per (row, column)
 // on top of the sum: shorter chunks keep many workgroups in flight.
